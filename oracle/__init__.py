@@ -1,0 +1,400 @@
+"""Python driver of the FP64 CPU oracle (oracle.c) of the PIC-MCC step.
+
+TEST INFRASTRUCTURE ONLY. Only tests/, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of bench.py may import this package. It shares no code
+with the GPU library and never imports it; it reads its inputs from plain
+numpy arrays and a configuration object with the attributes of
+``paper_2402_08404_amd.workloads.Config``.
+
+One step follows the order the paper gives for the PIC-MCC loop (Sec. 2.2 and
+Sec. 2.3.1): emission, push with boundary removal, collisions and field
+ionization, charge deposition, Poisson solve and node field.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+SP_E, SP_ION, SP_NEU = 0, 1, 2
+FREE, DIR0, DIRV = 0, 1, 2
+COLL_MCC1, COLL_MCC2, COLL_FI = 1, 2, 4
+COLL_ALL = 7
+ALIVE, CATHODE, ANODE, LATERAL, TIP = 0, 1, 2, 3, 4
+KIND_ELASTIC, KIND_IONIZE, KIND_CX, KIND_FI = 1, 2, 3, 4
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so with gcc (no fast math, no FMA
+    contraction)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+               "-Wall", "-o", _LIB_PATH + ".tmp", os.path.join(_HERE, "oracle.c"), "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Config(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("xs_n", C.c_int32),
+                ("h", C.c_double), ("tip_r", C.c_double), ("tip_h", C.c_double), ("dt", C.c_double),
+                ("phi_w", C.c_double), ("xi", C.c_double), ("m_ion", C.c_double),
+                ("xs_emin", C.c_double), ("xs_emax", C.c_double),
+                ("xs_el", C.POINTER(C.c_double)), ("xs_iz", C.POINTER(C.c_double)),
+                ("xs_cx", C.POINTER(C.c_double)), ("seed", C.c_uint64),
+                ("fn_rings", C.c_int32), ("fn_az", C.c_int32)]
+
+
+class _Species(C.Structure):
+    _fields_ = [("n", C.c_int64), ("cap", C.c_int64)] + \
+               [(k, C.POINTER(C.c_double)) for k in ("x", "y", "z", "vx", "vy", "vz")] + \
+               [("id", C.POINTER(C.c_uint32))]
+
+
+class _Event(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("id_a", C.c_uint32), ("id_b", C.c_uint32),
+                ("new_ion", C.c_uint32), ("new_e", C.c_uint32)]
+
+
+class _CollideOut(C.Structure):
+    _fields_ = [("ev", C.POINTER(_Event)), ("ev_cap", C.c_int64), ("n_ev", C.c_int64),
+                ("fragile", C.POINTER(C.c_uint32)), ("fr_cap", C.c_int64), ("n_fragile", C.c_int64),
+                ("n_kind", C.c_int64 * 5), ("n_bsi_skip", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        L = C.CDLL(_LIB_PATH)
+        dp, u8p, i64p, u32p = (np.ctypeslib.ndpointer(t, flags="C") for t in
+                               (np.float64, np.uint8, np.int64, np.uint32))
+        cfgp = C.POINTER(_Config)
+        L.orc_constants.argtypes = [dp]
+        L.orc_philox.argtypes = [u32p, u32p, u32p]
+        L.orc_uniform.argtypes = [C.c_uint32, C.c_uint32]
+        L.orc_uniform.restype = C.c_double
+        L.orc_inside_tip.argtypes = [cfgp, C.c_double, C.c_double, C.c_double]
+        L.orc_node_types.argtypes = [cfgp, u8p]
+        L.orc_rhs.argtypes = [cfgp, u8p, i64p, C.c_double, dp]
+        L.orc_apply_A.argtypes = [cfgp, u8p, dp, dp]
+        L.orc_solve.argtypes = [cfgp, u8p, i64p, C.c_double, dp, C.c_double, C.c_int, C.POINTER(C.c_double)]
+        L.orc_solve.restype = C.c_int
+        L.orc_field.argtypes = [cfgp, dp, dp]
+        L.orc_gather.argtypes = [cfgp, dp, C.c_double, C.c_double, C.c_double, dp]
+        L.orc_interp_phi.argtypes = [cfgp, dp, C.c_double, C.c_double, C.c_double]
+        L.orc_interp_phi.restype = C.c_double
+        L.orc_apex_field.argtypes = [cfgp, dp]
+        L.orc_apex_field.restype = C.c_double
+        L.orc_push.argtypes = [cfgp, dp, C.POINTER(_Species), C.c_double, C.c_double,
+                               np.ctypeslib.ndpointer(np.int32, flags="C")]
+        L.orc_deposit.argtypes = [cfgp, C.POINTER(_Species), C.c_int64, i64p]
+        L.orc_cell_of.argtypes = [cfgp, C.c_double, C.c_double, C.c_double]
+        L.orc_cell_of.restype = C.c_int64
+        L.orc_xs.argtypes = [cfgp, dp, C.c_double]
+        L.orc_xs.restype = C.c_double
+        L.orc_adk_rate.argtypes = [cfgp, C.c_double]
+        L.orc_adk_rate.restype = C.c_double
+        L.orc_fn_current.argtypes = [cfgp, C.c_double, C.POINTER(C.c_int)]
+        L.orc_fn_current.restype = C.c_double
+        L.orc_fn_patch_count.argtypes = [cfgp]
+        L.orc_fn_patch_count.restype = C.c_int64
+        L.orc_fn_patch.argtypes = [cfgp, C.c_int64, C.c_double, C.c_double, dp]
+        L.orc_fn_inject.argtypes = [cfgp, C.c_uint32, dp, C.POINTER(_Species), C.POINTER(C.c_uint32),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.orc_fn_inject.restype = C.c_int64
+        L.orc_collide.argtypes = [cfgp, C.c_uint32, C.c_int32, dp, C.POINTER(_Species),
+                                  C.POINTER(C.c_uint32), C.POINTER(_CollideOut)]
+        L.orc_collide.restype = C.c_int
+        L.orc_moments.argtypes = [cfgp, C.POINTER(_Species), dp, dp]
+        _lib = L
+    return _lib
+
+
+def make_config(cfg) -> tuple[_Config, list]:
+    """ctypes view of a workload configuration; the second value keeps the
+    table arrays alive."""
+    keep = [np.ascontiguousarray(t, dtype=np.float64) for t in (cfg.xs_el, cfg.xs_iz, cfg.xs_cx)]
+    dpp = C.POINTER(C.c_double)
+    c = _Config(nx=cfg.nx, ny=cfg.ny, nz=cfg.nz, xs_n=len(keep[0]), h=cfg.h, tip_r=cfg.tip_r,
+                tip_h=cfg.tip_h, dt=cfg.dt, phi_w=cfg.phi_w, xi=cfg.xi, m_ion=cfg.m_ion,
+                xs_emin=cfg.xs_emin, xs_emax=cfg.xs_emax,
+                xs_el=keep[0].ctypes.data_as(dpp), xs_iz=keep[1].ctypes.data_as(dpp),
+                xs_cx=keep[2].ctypes.data_as(dpp), seed=cfg.seed, fn_rings=cfg.fn_rings, fn_az=cfg.fn_az)
+    return c, keep
+
+
+def constants() -> dict:
+    out = np.zeros(8)
+    lib().orc_constants(out)
+    return dict(zip(("e", "m_e", "eps0", "h", "amu", "fn_a", "fn_b", "fn_cs2"), out))
+
+
+def philox(ctr, key) -> np.ndarray:
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox(np.asarray(ctr, np.uint32), np.asarray(key, np.uint32), out)
+    return out
+
+
+def uniform(hi: int, lo: int) -> float:
+    return lib().orc_uniform(hi, lo)
+
+
+class _SpeciesStore:
+    """Growable SoA arrays of one species (FP64 grid units, uint32 ids)."""
+
+    def __init__(self, cap: int):
+        self.cap = int(cap)
+        self.n = 0
+        self.a = {k: np.zeros(self.cap) for k in ("x", "y", "z", "vx", "vy", "vz")}
+        self.id = np.zeros(self.cap, np.uint32)
+
+    def view(self) -> _Species:
+        dpp = C.POINTER(C.c_double)
+        s = _Species(n=self.n, cap=self.cap, id=self.id.ctypes.data_as(C.POINTER(C.c_uint32)),
+                     **{k: v.ctypes.data_as(dpp) for k, v in self.a.items()})
+        return s
+
+    def ensure(self, extra: int):
+        if self.n + extra <= self.cap:
+            return
+        new = max(2 * self.cap, self.n + extra + 1024)
+        for k in self.a:
+            b = np.zeros(new)
+            b[: self.n] = self.a[k][: self.n]
+            self.a[k] = b
+        b = np.zeros(new, np.uint32)
+        b[: self.n] = self.id[: self.n]
+        self.id = b
+        self.cap = new
+
+    def keep(self, mask: np.ndarray):
+        m = int(mask.sum())
+        for k in self.a:
+            self.a[k][:m] = self.a[k][: self.n][mask]
+        self.id[:m] = self.id[: self.n][mask]
+        self.n = m
+
+    def arrays(self) -> dict:
+        d = {k: v[: self.n].copy() for k, v in self.a.items()}
+        d["id"] = self.id[: self.n].copy()
+        return d
+
+
+class Oracle:
+    """The whole PIC-MCC state of one instance, advanced step by step."""
+
+    def __init__(self, cfg, laplace_rtol: float = 1e-13):
+        self.cfg = cfg
+        self.c, self._keep = make_config(cfg)
+        self.L = lib()
+        N = cfg.nx * cfg.ny * cfg.nz
+        self.type = np.zeros(N, np.uint8)
+        self.L.orc_node_types(C.byref(self.c), self.type)
+        # Laplace problem with a unit anode: the anode voltage that gives the
+        # requested apex field, and the Shockley-Ramo weighting field.
+        self.phi1 = np.zeros(N)
+        rr = C.c_double()
+        self.laplace_iters = self.L.orc_solve(C.byref(self.c), self.type, np.zeros(N, np.int64), 1.0,
+                                              self.phi1, laplace_rtol, 100000, C.byref(rr))
+        self.F1 = self.L.orc_apex_field(C.byref(self.c), self.phi1)
+        self.V0 = cfg.apex_field / self.F1
+        self.E0 = np.zeros(3 * N)
+        self.L.orc_field(C.byref(self.c), self.phi1, self.E0)
+        self.phi = self.phi1 * self.V0
+        self.E = np.zeros(3 * N)
+        self.L.orc_field(C.byref(self.c), self.phi, self.E)
+        self.Q = np.zeros(N, np.int64)
+        self.sp = [_SpeciesStore(1024) for _ in range(3)]
+        self.next_id = 0
+        self.step_no = 0
+        self.masses = (constants()["m_e"], cfg.m_ion, cfg.m_ion)
+        self.charges = (-constants()["e"], constants()["e"], 0.0)
+        self.absorbed = np.zeros((3, 5), np.int64)
+        self.events = np.zeros(5, np.int64)
+        self.injected = 0
+        self.n_expected = 0.0
+        self.fn_clamped = 0
+        self.bsi_skips = 0
+        self.last_events = []
+        self.last_fragile = set()
+        self.last_solve = (0, 0.0)
+
+    # -- state -------------------------------------------------------------
+    def load(self, load: dict):
+        """Append an explicit particle load (dict species -> arrays in grid
+        units); ids are numbered in load order: electrons, ions, neutrals."""
+        for s, name in enumerate(("e", "ion", "neutral")):
+            if name not in load:
+                continue
+            a = load[name]
+            n = len(a["x"])
+            st = self.sp[s]
+            st.ensure(n)
+            for k in ("x", "y", "z", "vx", "vy", "vz"):
+                st.a[k][st.n: st.n + n] = np.asarray(a[k], np.float64)
+            st.id[st.n: st.n + n] = np.arange(self.next_id, self.next_id + n, dtype=np.uint32)
+            st.n += n
+            self.next_id += n
+
+    def state(self) -> list:
+        return [s.arrays() for s in self.sp]
+
+    def _views(self):
+        arr = (_Species * 3)(*[s.view() for s in self.sp])
+        return arr
+
+    def _pull(self, arr):
+        for s, v in zip(self.sp, arr):
+            s.n = int(v.n)
+
+    # -- stages ------------------------------------------------------------
+    def set_phi(self, phi: np.ndarray):
+        self.phi = np.ascontiguousarray(phi, dtype=np.float64).copy()
+        self.field()
+
+    def field(self):
+        self.L.orc_field(C.byref(self.c), self.phi, self.E)
+
+    def deposit(self) -> np.ndarray:
+        self.Q[:] = 0
+        for s, sign in ((SP_E, -1), (SP_ION, 1)):
+            v = self.sp[s].view()
+            self.L.orc_deposit(C.byref(self.c), C.byref(v), sign, self.Q)
+        return self.Q
+
+    def solve(self, rtol: float = 1e-8, maxit: int = 100000, guess: str = "previous"):
+        if guess == "zero":
+            self.phi = np.zeros_like(self.phi)
+        rr = C.c_double()
+        it = self.L.orc_solve(C.byref(self.c), self.type, self.Q, self.V0, self.phi, rtol, maxit, C.byref(rr))
+        self.last_solve = (it, rr.value)
+        self.field()
+        return it, rr.value
+
+    def inject(self) -> int:
+        st = self.sp[SP_E]
+        np_ = self.L.orc_fn_patch_count(C.byref(self.c))
+        st.ensure(int(np_) * 4 + 64)
+        v = st.view()
+        nid = C.c_uint32(self.next_id)
+        nexp = C.c_double(0.0)
+        ncl = C.c_int64(0)
+        k = self.L.orc_fn_inject(C.byref(self.c), self.step_no, self.phi, C.byref(v), C.byref(nid),
+                                 C.byref(nexp), C.byref(ncl))
+        if k < 0:
+            raise RuntimeError("oracle: injection capacity")
+        st.n = int(v.n)
+        self.next_id = nid.value
+        self.injected += k
+        self.n_expected += nexp.value
+        self.fn_clamped += ncl.value
+        return k
+
+    def push(self) -> list:
+        codes = []
+        for s in range(3):
+            st = self.sp[s]
+            code = np.zeros(max(st.n, 1), np.int32)
+            v = st.view()
+            self.L.orc_push(C.byref(self.c), self.E, C.byref(v), self.charges[s], self.masses[s], code)
+            code = code[: st.n]
+            for k in range(1, 5):
+                self.absorbed[s, k] += int((code == k).sum())
+            st.keep(code == ALIVE)
+            codes.append(code)
+        return codes
+
+    def collide(self, flags: int = COLL_ALL):
+        n_neu = self.sp[SP_NEU].n
+        for s in (SP_E, SP_ION):
+            self.sp[s].ensure(n_neu + 1)
+        cap = 2 * (n_neu + self.sp[SP_E].n + self.sp[SP_ION].n) + 16
+        ev = (_Event * cap)()
+        fr = np.zeros(cap, np.uint32)
+        out = _CollideOut(ev=ev, ev_cap=cap, fragile=fr.ctypes.data_as(C.POINTER(C.c_uint32)), fr_cap=cap)
+        arr = self._views()
+        nid = C.c_uint32(self.next_id)
+        rc = self.L.orc_collide(C.byref(self.c), self.step_no, flags, self.E, arr, C.byref(nid), C.byref(out))
+        if rc != 0:
+            raise RuntimeError("oracle: collision product capacity")
+        self._pull(arr)
+        self.next_id = nid.value
+        n = int(out.n_ev)
+        self.last_events = [(ev[i].kind, ev[i].id_a, ev[i].id_b, ev[i].new_ion, ev[i].new_e) for i in range(n)]
+        self.last_fragile = set(int(x) for x in fr[: int(out.n_fragile)])
+        for k in range(5):
+            self.events[k] += out.n_kind[k]
+        self.bsi_skips += int(out.n_bsi_skip)
+        return self.last_events
+
+    def step(self, rtol: float = 1e-8, inject: bool = True, collide_flags: int = COLL_ALL,
+             solve: bool = True):
+        if inject:
+            self.inject()
+        self.push()
+        if collide_flags:
+            self.collide(collide_flags)
+        self.deposit()
+        if solve:
+            self.solve(rtol=rtol)
+        self.step_no += 1
+
+    def moments(self) -> dict:
+        out = np.zeros(8)
+        arr = self._views()
+        self.L.orc_moments(C.byref(self.c), arr, self.E0, out)
+        return {"ke": out[0:3].copy(), "i_sr": float(out[3]), "n": out[4:7].astype(np.int64),
+                "q_total": int(self.Q.sum()), "absorbed": self.absorbed.copy(),
+                "events": self.events.copy(), "injected": self.injected}
+
+    # -- helpers for tests ----------------------------------------------------
+    def gather(self, E: np.ndarray, X, Y, Z) -> np.ndarray:
+        out = np.zeros(3)
+        self.L.orc_gather(C.byref(self.c), E, X, Y, Z, out)
+        return out
+
+    def interp_phi(self, phi, X, Y, Z) -> float:
+        return self.L.orc_interp_phi(C.byref(self.c), np.ascontiguousarray(phi, np.float64), X, Y, Z)
+
+    def adk_rate(self, E_GVm: float) -> float:
+        return self.L.orc_adk_rate(C.byref(self.c), E_GVm)
+
+    def fn_current(self, F: float) -> float:
+        cl = C.c_int(0)
+        return self.L.orc_fn_current(C.byref(self.c), F, C.byref(cl))
+
+    def xs(self, which: str, E: float) -> float:
+        tab = {"el": self._keep[0], "iz": self._keep[1], "cx": self._keep[2]}[which]
+        return self.L.orc_xs(C.byref(self.c), tab, E)
+
+    def apply_A(self, x: np.ndarray) -> np.ndarray:
+        y = np.zeros_like(x)
+        self.L.orc_apply_A(C.byref(self.c), self.type, np.ascontiguousarray(x, np.float64), y)
+        return y
+
+    def rhs(self, Q: np.ndarray, V0: float) -> np.ndarray:
+        b = np.zeros(len(Q))
+        self.L.orc_rhs(C.byref(self.c), self.type, np.ascontiguousarray(Q, np.int64), V0, b)
+        return b
+
+    def inside_tip(self, X, Y, Z) -> bool:
+        return bool(self.L.orc_inside_tip(C.byref(self.c), X, Y, Z))
+
+    def fn_patches(self, ua=0.5, ub=0.5) -> np.ndarray:
+        n = int(self.L.orc_fn_patch_count(C.byref(self.c)))
+        out = np.zeros((n, 8))
+        buf = np.zeros(8)
+        for p in range(n):
+            self.L.orc_fn_patch(C.byref(self.c), p, ua, ub, buf)
+            out[p] = buf
+        return out

@@ -1,0 +1,707 @@
+"""Pins of the FP64 CPU oracle against what the paper and mathematics fix,
+independently of the oracle's own code: a second Philox implementation,
+CODATA and published Fowler-Nordheim constants, the exact Schottky-Nordheim
+barrier functions, the atomic-units ADK rate, closed-form potentials and
+trajectories, and collision statistics with closed-form means.
+
+All tests here run on the CPU."""
+import math
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+import scipy.constants as sc
+import scipy.special as ss
+
+import oracle
+from paper_2402_08404_amd import workloads as W
+
+
+def _no_tip(nx=16, ny=16, nz=32, h=2e-9):
+    """A configuration whose tip is too thin to cover any node (the tip axis
+    sits between nodes), i.e. two parallel plates."""
+    return W.small(nx=nx, ny=ny, nz=nz, h=h, tip_r=0.05 * h, tip_h=0.1 * h)
+
+
+# --------------------------------------------------------------------------
+# Random numbers
+
+
+def test_philox_matches_rocrand(tmp_path):
+    """Philox4x32-10 against rocRAND's independent implementation (its
+    header-only engine, compiled for the host)."""
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc) or not os.path.exists("/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"):
+        pytest.skip("rocRAND headers / hipcc not available")
+    rng = np.random.default_rng(5)
+    cases = []
+    for _ in range(24):
+        key = int(rng.integers(0, 2**63))
+        c = [int(x) for x in rng.integers(0, 2**30, size=4)]
+        cases.append((key, c))
+    cases.append((0, [0, 0, 0, 0]))
+    src = ["#include <rocrand/rocrand_philox4x32_10.h>", "#include <cstdio>", "int main(){",
+           "rocrand_state_philox4x32_10 s; uint4 r;"]
+    for key, c in cases:
+        sub = c[2] | (c[3] << 32)
+        off = 4 * (c[0] | (c[1] << 32))
+        src.append(f"rocrand_init({key}ULL, {sub}ULL, {off}ULL, &s); r = rocrand4(&s);"
+                   ' printf("%u %u %u %u\\n", r.x, r.y, r.z, r.w);')
+    src.append("return 0; }")
+    (tmp_path / "p.cpp").write_text("\n".join(src))
+    exe = tmp_path / "p"
+    r = subprocess.run([hipcc, "-x", "hip", "--offload-arch=gfx950", "-O1", "-o", str(exe), str(tmp_path / "p.cpp")],
+                       capture_output=True, text=True, timeout=300)
+    if r.returncode != 0:
+        pytest.skip("could not build the rocRAND probe: " + r.stderr[-400:])
+    lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    for (key, c), line in zip(cases, lines):
+        want = [int(x) for x in line.split()]
+        got = oracle.philox(c, [key & 0xFFFFFFFF, key >> 32])
+        assert list(got) == want, (key, c)
+
+
+def test_uniform_closed_form():
+    assert oracle.uniform(0, 0) == 0.5 * 2.0**-52
+    assert oracle.uniform(0xFFFFFFFF, 0xFFFFFFFF) == 1.0 - 2.0**-53
+    assert oracle.uniform(0x80000000, 0) == 0.5 + 0.5 * 2.0**-52
+    # only the top 20 bits of the low word enter
+    assert oracle.uniform(7, 0xFFF) == oracle.uniform(7, 0)
+
+
+def test_philox_uniformity():
+    """Chi-square over 64 bins of 200k uniforms, and no correlation between
+    neighbouring counters."""
+    n = 100000
+    u = np.empty(2 * n)
+    for i in range(n):
+        w = oracle.philox([i, 17, 3, 0], [1, 0])
+        u[2 * i] = oracle.uniform(int(w[0]), int(w[1]))
+        u[2 * i + 1] = oracle.uniform(int(w[2]), int(w[3]))
+    hist = np.bincount((u * 64).astype(int), minlength=64)
+    e = len(u) / 64
+    chi2 = ((hist - e) ** 2 / e).sum()
+    assert chi2 < 120  # 63 dof: P(chi2 > 120) ~ 2e-5
+    assert abs(np.corrcoef(u[:-2], u[2:])[0, 1]) < 0.01
+    assert abs(u.mean() - 0.5) < 4 * math.sqrt(1 / 12 / len(u))
+
+
+# --------------------------------------------------------------------------
+# Constants and closed-form rates
+
+
+def test_codata_constants():
+    k = oracle.constants()
+    assert k["e"] == sc.e
+    assert k["m_e"] == sc.m_e
+    assert k["eps0"] == sc.epsilon_0
+    assert k["h"] == sc.h
+    assert k["amu"] == sc.physical_constants["atomic mass constant"][0]
+
+
+def test_fowler_nordheim_constants_published():
+    """First and second Fowler-Nordheim constants and the Schottky constant as
+    published by Forbes and Deane (Proc. R. Soc. A 463, 2007)."""
+    k = oracle.constants()
+    assert k["fn_a"] == pytest.approx(1.541434e-6, rel=2e-6)          # A eV V^-2
+    assert k["fn_b"] * 1e-9 == pytest.approx(6.830890, rel=2e-6)     # eV^-3/2 V nm^-1
+    assert k["fn_cs2"] * 1e9 == pytest.approx(1.439964, rel=2e-6)    # eV^2 V^-1 nm
+
+
+def _exact_v_t(f):
+    """Schottky-Nordheim barrier functions through complete elliptic
+    integrals (parameter m = k^2), with y = sqrt(f)."""
+    y = math.sqrt(f)
+    m = (1 - y) / (1 + y)
+    K, E = ss.ellipk(m), ss.ellipe(m)
+    v = math.sqrt(1 + y) * (E - y * K)
+    t = ((1 + y) * E - y * K) / math.sqrt(1 + y)
+    return v, t
+
+
+@pytest.mark.parametrize("F", [3e9, 5e9, 8e9, 10e9, 12e9, 14e9])
+def test_fn_current_vs_exact_barrier(F):
+    """Murphy-Good J with Forbes' approximations against J with the exact
+    barrier functions: the approximations are within 0.0025 in v and 0.0042 in
+    t on 0 < f <= 1, which bounds the relative difference of J."""
+    o = oracle.Oracle(W.small(nz=16, tip_h=8e-9))
+    phi = o.cfg.phi_w
+    a, b, cs2 = 1.541434e-6, 6.830890e9, 1.439964e-9
+    f = cs2 * F / phi**2
+    v, t = _exact_v_t(f)
+    J_exact = a * F**2 / (phi * t * t) * math.exp(-v * b * phi**1.5 / F)
+    bound = 0.0025 * b * phi**1.5 / F + 2 * 0.0042 / t + 1e-5
+    assert abs(o.fn_current(F) / J_exact - 1) <= bound
+
+
+def test_fn_no_emission_without_field():
+    o = oracle.Oracle(W.small(nz=16, tip_h=8e-9))
+    assert o.fn_current(0.0) == 0.0 and o.fn_current(-1e9) == 0.0
+
+
+def _adk_atomic_units(E_GVm, xi_eV):
+    """ADK rate of a hydrogen-like level with l* = n* - 1, m = 0, in atomic
+    units, converted with CODATA: w = 2^{2n}/(n Gamma(2n)) I_p
+    (2 (2 I_p)^{3/2}/F)^{2n-1} exp(-2 (2 I_p)^{3/2} / (3F))."""
+    Ip = xi_eV / sc.physical_constants["Hartree energy in eV"][0]
+    n = 1.0 / math.sqrt(2 * Ip)
+    F = E_GVm * 1e9 / sc.physical_constants["atomic unit of electric field"][0]
+    w = 2 ** (2 * n) / (n * math.gamma(2 * n)) * Ip * (2 * (2 * Ip) ** 1.5 / F) ** (2 * n - 1) \
+        * math.exp(-2 * (2 * Ip) ** 1.5 / (3 * F))
+    return w / sc.physical_constants["atomic unit of time"][0] * 1e-15
+
+
+@pytest.mark.parametrize("E", [6.0, 8.0, 10.0, 12.0, 14.0, 20.0, 30.0])
+def test_adk_rate_vs_atomic_units(E):
+    """Eq. dfi is the atomic-units ADK formula with rounded coefficients
+    (1.52, 20.5, 6.83, 3.69): the two agree to about 1%."""
+    o = oracle.Oracle(W.small(nz=16, tip_h=8e-9))
+    assert o.adk_rate(E) == pytest.approx(_adk_atomic_units(E, o.cfg.xi), rel=0.015)
+    assert o.adk_rate(0.0) == 0.0
+
+
+def test_cross_section_tables():
+    cfg = W.small(tables="synthetic")
+    o = oracle.Oracle(cfg)
+    E = cfg.xs_emin * (cfg.xs_emax / cfg.xs_emin) ** (np.arange(256) / 255)
+    for k in (0, 17, 100, 255):   # nodes are reproduced
+        assert o.xs("el", E[k]) == pytest.approx(cfg.xs_el[k], rel=1e-12)
+    # linear in ln E between nodes
+    Em = math.sqrt(E[40] * E[41])
+    assert o.xs("cx", Em) == pytest.approx(0.5 * (cfg.xs_cx[40] + cfg.xs_cx[41]), rel=1e-9)
+    # clamped outside
+    assert o.xs("el", 1e-5) == cfg.xs_el[0] and o.xs("el", 1e7) == cfg.xs_el[-1]
+    # a flat table is returned exactly
+    o2 = oracle.Oracle(W.small())
+    assert o2.xs("el", 3.3) == 5e-20
+
+
+# --------------------------------------------------------------------------
+# Geometry and Poisson
+
+
+def test_node_types_brute_force():
+    """The Dirichlet mask against the tip written as a capsule: all points
+    within distance r of the axis segment from z=0 to z=H-r, above the
+    cathode."""
+    cfg = W.tiny()
+    o = oracle.Oracle(cfg)
+    t = o.type.reshape(cfg.nz, cfg.ny, cfg.nx)
+    R, H = cfg.tip_r / cfg.h, cfg.tip_h / cfg.h
+    xc, yc = (cfg.nx - 1) / 2, (cfg.ny - 1) / 2
+    k, j, i = np.meshgrid(np.arange(cfg.nz), np.arange(cfg.ny), np.arange(cfg.nx), indexing="ij")
+    zs = np.clip(k, 0, H - R)
+    d = np.sqrt((i - xc) ** 2 + (j - yc) ** 2 + (k - zs) ** 2)
+    tip = (d <= R + 1e-12)
+    want = np.where(k == 0, 1, np.where(k == cfg.nz - 1, 2, np.where(tip, 1, 0)))
+    assert np.array_equal(t, want)
+    assert np.array_equal(t, t.transpose(0, 2, 1))      # x <-> y mirror
+    assert np.array_equal(t, t[:, ::-1, ::-1])           # point reflection about the axis
+    assert (t[1:-1] == 1).sum() > 0
+
+
+def test_parallel_plates_linear_potential():
+    """Without a tip or charge the discrete solution is exactly the linear
+    ramp V0 z/L (the FV operator reproduces linear functions)."""
+    cfg = _no_tip()
+    o = oracle.Oracle(cfg)
+    assert (o.type.reshape(cfg.nz, -1)[1:-1] == 0).all()
+    k = np.repeat(np.arange(cfg.nz), cfg.nx * cfg.ny)
+    np.testing.assert_allclose(o.phi1, k / (cfg.nz - 1), rtol=0, atol=1e-12)
+    # field and Shockley-Ramo weighting field are uniform 1/L
+    E0 = o.E0.reshape(-1, 3)
+    np.testing.assert_allclose(E0[:, 2], -1.0 / ((cfg.nz - 1) * cfg.h), rtol=1e-10)
+    np.testing.assert_allclose(E0[:, :2], 0.0, atol=1e-3)
+
+
+def _mms_error(n):
+    """Max error of the discrete solution against the continuum potential
+    phi = V z/L + sin(pi z/L) cos(2 pi x/Lx) cos(2 pi y/Ly) whose charge is
+    deposited as node charges rho * (control volume)."""
+    h = 8e-9 / n
+    cfg = W.small(nx=n + 1, ny=n + 1, nz=2 * n + 1, h=h, tip_r=0.05 * h, tip_h=0.1 * h)
+    o = oracle.Oracle(cfg)
+    Lx, Lz = n * h, 2 * n * h
+    V = 2.0
+    z = np.arange(cfg.nz) * h
+    y = np.arange(cfg.ny) * h
+    x = np.arange(cfg.nx) * h
+    Z, Y, X = np.meshgrid(z, y, x, indexing="ij")
+    S = np.sin(np.pi * Z / Lz) * np.cos(2 * np.pi * X / Lx) * np.cos(2 * np.pi * Y / Lx)
+    exact = V * Z / Lz + S
+    lap = -(np.pi / Lz) ** 2 - 2 * (2 * np.pi / Lx) ** 2
+    rho = -sc.epsilon_0 * lap * S                       # -eps0 laplace(phi)
+    wx = np.where((np.arange(cfg.nx) == 0) | (np.arange(cfg.nx) == cfg.nx - 1), 0.5, 1.0)
+    vol = h**3 * wx[None, None, :] * wx[None, :, None]
+    Q = np.rint(rho * vol / (sc.e * 2.0**-40)).astype(np.int64).reshape(-1)
+    phi = np.zeros(cfg.n_nodes)
+    rr = oracle.C.c_double()
+    o.L.orc_solve(oracle.C.byref(o.c), o.type, Q, V, phi, 1e-13, 100000, oracle.C.byref(rr))
+    return np.abs(phi - exact.reshape(-1)).max()
+
+
+def test_poisson_manufactured_second_order():
+    e1, e2 = _mms_error(8), _mms_error(16)
+    assert e1 < 0.1
+    assert 3.3 < e1 / e2 < 4.8, (e1, e2)
+
+
+def test_cg_matches_direct_solve():
+    """The oracle's CG against scipy's sparse direct solver on the operator
+    assembled column by column from the oracle's own matrix product; the
+    assembled matrix must be symmetric."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    cfg = W.small(nx=8, ny=8, nz=16, h=2e-9, tip_r=3e-9, tip_h=14e-9)
+    o = oracle.Oracle(cfg)
+    free = np.flatnonzero(o.type == 0)
+    cols = []
+    for n in free:
+        e = np.zeros(cfg.n_nodes)
+        e[n] = 1.0
+        cols.append(o.apply_A(e)[free])
+    A = np.array(cols).T
+    assert np.abs(A - A.T).max() == 0.0
+    assert np.linalg.eigvalsh(A).min() > 0
+    rng = np.random.default_rng(0)
+    Q = rng.integers(-2**44, 2**44, size=cfg.n_nodes).astype(np.int64)
+    b = o.rhs(Q, 3.0)[free]
+    x = spl.spsolve(sp.csr_matrix(A), b)
+    phi = np.zeros(cfg.n_nodes)
+    rr = oracle.C.c_double()
+    o.L.orc_solve(oracle.C.byref(o.c), o.type, Q, 3.0, phi, 1e-14, 10000, oracle.C.byref(rr))
+    np.testing.assert_allclose(phi[free], x, rtol=0, atol=1e-10 * np.abs(x).max())
+    assert (phi[o.type == 2] == 3.0).all() and (phi[o.type == 1] == 0.0).all()
+
+
+def test_apex_field_calibration():
+    """V0 is chosen so that the Laplace field one spacing above the apex is
+    the requested local field; the field grows towards the apex."""
+    cfg = W.tiny()
+    o = oracle.Oracle(cfg)
+    xc = (cfg.nx - 1) / 2
+    H = cfg.tip_h / cfg.h
+    assert o.interp_phi(o.phi, xc, xc, H + 1) / cfg.h == pytest.approx(cfg.apex_field, rel=1e-12)
+    # the enhanced apex field exceeds the plate field V0/L
+    assert cfg.apex_field > o.V0 / ((cfg.nz - 1) * cfg.h)
+
+
+# --------------------------------------------------------------------------
+# Field, gather, push
+
+
+def test_linear_potential_field_and_gather_exact():
+    cfg = W.small()
+    o = oracle.Oracle(cfg)
+    k, j, i = np.meshgrid(np.arange(cfg.nz), np.arange(cfg.ny), np.arange(cfg.nx), indexing="ij")
+    a, bx, by, bz = 1.0, 0.3, -0.2, 0.7
+    o.set_phi((a + bx * i + by * j + bz * k).reshape(-1).astype(float))
+    rng = np.random.default_rng(1)
+    for _ in range(50):
+        X = rng.uniform(1, cfg.nx - 2)
+        Y = rng.uniform(1, cfg.ny - 2)
+        Z = rng.uniform(0, cfg.nz - 1 - 1e-9)
+        e = o.gather(o.E, X, Y, Z)
+        np.testing.assert_allclose(e, [-bx / cfg.h, -by / cfg.h, -bz / cfg.h], rtol=1e-12)
+    E = o.E.reshape(cfg.nz, cfg.ny, cfg.nx, 3)
+    assert (E[:, :, 0, 0] == 0).all() and (E[:, 0, :, 1] == 0).all()   # zero normal field on lateral faces
+
+
+def test_ballistic_constant_field():
+    """Leapfrog is exact for a constant force: with v^{-1/2} = v0 - a dt/2 the
+    position after n steps is x0 + v0 t + a t^2/2 (to rounding)."""
+    cfg = _no_tip()
+    o = oracle.Oracle(cfg)
+    L = (cfg.nz - 1) * cfg.h
+    V = 50.0
+    o.set_phi(np.repeat(np.arange(cfg.nz) / (cfg.nz - 1) * V, cfg.nx * cfg.ny))
+    Ez = -V / L
+    m, q = cfg.m_ion, sc.e
+    a = q / m * Ez                          # ion accelerated towards the cathode
+    x0 = np.array([7.3, 8.1, 25.0])
+    v0 = np.array([300.0, -200.0, 100.0])   # m/s
+    s = cfg.dt / cfg.h
+    load = {"ion": {"x": [x0[0]], "y": [x0[1]], "z": [x0[2]],
+                    "vx": [v0[0] * s], "vy": [v0[1] * s], "vz": [(v0[2] - a * cfg.dt / 2) * s]}}
+    o.load(load)
+    n = 200
+    for _ in range(n):
+        o.push()
+    t = n * cfg.dt
+    st = o.state()[oracle.SP_ION]
+    want = x0 + np.array([v0[0] * t, v0[1] * t, v0[2] * t + 0.5 * a * t * t]) / cfg.h
+    np.testing.assert_allclose([st["x"][0], st["y"][0], st["z"][0]], want, rtol=1e-12)
+    assert st["vz"][0] == pytest.approx((v0[2] + a * (t - cfg.dt / 2)) * s, rel=1e-12)
+
+
+def test_absorption_codes():
+    cfg = W.small()
+    o = oracle.Oracle(cfg)
+    o.set_phi(np.zeros(cfg.n_nodes))
+    xc = (cfg.nx - 1) / 2
+    R, H = cfg.tip_r / cfg.h, cfg.tip_h / cfg.h
+    pts = [  # (x, y, z, vx, vy, vz) -> code
+        ((3.0, 3.0, 0.2, 0.0, 0.0, -0.3), oracle.CATHODE),
+        ((3.0, 3.0, 0.2, 0.0, 0.0, -0.2), oracle.CATHODE),       # lands exactly on z = 0
+        ((3.0, 3.0, cfg.nz - 1.5, 0.0, 0.0, 0.6), oracle.ANODE),
+        ((0.2, 3.0, 5.0, -0.3, 0.0, 0.0), oracle.LATERAL),
+        ((cfg.nx - 1.5, 3.0, 5.0, 0.5, 0.0, 0.0), oracle.LATERAL),  # X = nx-1 is outside
+        ((xc + R + 0.3, xc, 5.0, -0.5, 0.0, 0.0), oracle.TIP),
+        ((xc, xc, H + 0.4, 0.0, 0.0, -0.5), oracle.TIP),
+        ((xc, xc, H + 0.4, 0.0, 0.0, -0.3), oracle.ALIVE),
+        ((0.5, 3.0, 5.0, -0.5, 0.0, 0.0), oracle.ALIVE),          # lands on X = 0, inside
+    ]
+    arr = np.array([p for p, _ in pts])
+    o.load({"neutral": {k: arr[:, i] for i, k in enumerate(("x", "y", "z", "vx", "vy", "vz"))}})
+    codes = o.push()[oracle.SP_NEU]
+    assert list(codes) == [c for _, c in pts]
+
+
+# --------------------------------------------------------------------------
+# Deposit
+
+
+def test_deposit_conservation_and_cic():
+    cfg = W.small()
+    o = oracle.Oracle(cfg)
+    ld = W.initial_load(cfg, counts=(3000, 1000, 0), region="box")
+    o.load(ld)
+    Q = o.deposit().copy()
+    assert Q.sum() == 2**40 * (1000 - 3000)
+    # against textbook cloud-in-cell in FP64: per particle and node the
+    # quantized weight differs from the exact product by < 3 * 2^-13
+    exact = np.zeros(cfg.n_nodes)
+    for s, sign in ((0, -1.0), (1, 1.0)):
+        st = o.state()[s]
+        for X, Y, Z in zip(st["x"], st["y"], st["z"]):
+            i, j, k = int(X), int(Y), int(Z)
+            fx, fy, fz = X - i, Y - j, Z - k
+            for di, wx in ((0, 1 - fx), (1, fx)):
+                for dj, wy in ((0, 1 - fy), (1, fy)):
+                    for dk, wz in ((0, 1 - fz), (1, fz)):
+                        exact[((k + dk) * cfg.ny + j + dj) * cfg.nx + i + di] += sign * wx * wy * wz
+    cnt = np.zeros(cfg.n_nodes)
+    for s in (0, 1):
+        st = o.state()[s]
+        for X, Y, Z in zip(st["x"], st["y"], st["z"]):
+            i, j, k = int(X), int(Y), int(Z)
+            for dk in (0, 1):
+                for dj in (0, 1):
+                    for di in (0, 1):
+                        cnt[((k + dk) * cfg.ny + j + dj) * cfg.nx + i + di] += 1
+    assert (np.abs(Q * 2.0**-40 - exact) <= cnt * 3 * 2.0**-13 + 1e-15).all()
+
+
+def test_deposit_special_positions_and_permutation():
+    cfg = W.small()
+    o = oracle.Oracle(cfg)
+    o.load({"ion": {"x": [3.0, 5.5], "y": [4.0, 6.5], "z": [7.0, 9.5], "vx": [0, 0], "vy": [0, 0], "vz": [0, 0]}})
+    Q = o.deposit().reshape(cfg.nz, cfg.ny, cfg.nx)
+    assert Q[7, 4, 3] == 2**40                       # on a node: all charge there
+    assert (Q[9:11, 6:8, 5:7] == 2**37).all()          # cell centre: eight equal shares
+    assert np.count_nonzero(Q) == 9
+    # permutation invariance (integer sums)
+    o2 = oracle.Oracle(cfg)
+    ld = W.initial_load(cfg, counts=(2000, 500, 0), region="box", seed=3)
+    o2.load(ld)
+    Qa = o2.deposit().copy()
+    perm = np.random.default_rng(0).permutation(2000)
+    ld["e"] = {k: v[perm] for k, v in ld["e"].items()}
+    o3 = oracle.Oracle(cfg)
+    o3.load(ld)
+    assert np.array_equal(o3.deposit(), Qa)
+
+
+# --------------------------------------------------------------------------
+# Collisions
+
+
+def _cells_load(cfg, ncells, n_a, n_b, speed_grid, rng, a="e"):
+    """n_a particles of species a moving with a given speed in random
+    directions and n_b resting neutrals in each of ncells distinct cells."""
+    cells = rng.choice((cfg.nx - 1) * (cfg.ny - 1) * (cfg.nz - 1), size=ncells, replace=False)
+    i = cells % (cfg.nx - 1)
+    j = (cells // (cfg.nx - 1)) % (cfg.ny - 1)
+    k = cells // ((cfg.nx - 1) * (cfg.ny - 1))
+
+    def fill(n, moving):
+        X = np.repeat(i, n) + rng.uniform(0.05, 0.95, ncells * n)
+        Y = np.repeat(j, n) + rng.uniform(0.05, 0.95, ncells * n)
+        Z = np.repeat(k, n) + rng.uniform(0.05, 0.95, ncells * n)
+        if moving:
+            d = rng.standard_normal((ncells * n, 3))
+            d /= np.linalg.norm(d, axis=1)[:, None]
+            v = d * speed_grid
+        else:
+            v = np.zeros((ncells * n, 3))
+        return {"x": X, "y": Y, "z": Z, "vx": v[:, 0], "vy": v[:, 1], "vz": v[:, 2]}
+
+    return {a: fill(n_a, True), "neutral": fill(n_b, False)}
+
+
+def _big_xs(cfg):
+    cfg.xs_el, cfg.xs_iz, cfg.xs_cx = W.constant_tables(4e-19, 1e-19, 6e-19)
+    return cfg
+
+
+def test_mcc_rate_electron_projectile():
+    """One electron and four resting neutrals per cell, all electrons at the
+    same speed u: each cell collides with P = 1 - exp(-u (4/h^3) sigma dt)
+    (Eq. colp with n the target density) and the process split follows the
+    cross sections."""
+    cfg = _big_xs(W.small(nx=24, ny=24, nz=24, tip_h=8e-9))
+    o = oracle.Oracle(cfg)
+    rng = np.random.default_rng(11)
+    u = 2.0e7                                 # m/s, 1.14 keV
+    ncell = 4000
+    o.load(_cells_load(cfg, ncell, 1, 4, u * cfg.dt / cfg.h, rng))
+    o.collide(oracle.COLL_MCC1)
+    n = 4 / cfg.h**3
+    P = 1 - math.exp(-u * n * 5e-19 * cfg.dt)
+    k = len(o.last_events)
+    assert abs(k - ncell * P) < 3.5 * math.sqrt(ncell * P * (1 - P)), (k, ncell * P)
+    niz = sum(1 for e in o.last_events if e[0] == oracle.KIND_IONIZE)
+    assert abs(niz - k * 0.2) < 3.5 * math.sqrt(k * 0.2 * 0.8)
+
+
+def test_mcc_rate_neutral_projectile():
+    """Three electrons and one neutral per cell: the neutral is the projectile
+    and n counts the three electrons."""
+    cfg = _big_xs(W.small(nx=24, ny=24, nz=24, tip_h=8e-9))
+    o = oracle.Oracle(cfg)
+    rng = np.random.default_rng(12)
+    u = 1.0e7
+    ncell = 4000
+    o.load(_cells_load(cfg, ncell, 3, 1, u * cfg.dt / cfg.h, rng))
+    o.collide(oracle.COLL_MCC1)
+    P = 1 - math.exp(-u * (3 / cfg.h**3) * 5e-19 * cfg.dt)
+    k = len(o.last_events)
+    assert abs(k - ncell * P) < 3.5 * math.sqrt(ncell * P * (1 - P)), (k, ncell * P)
+    # every neutral took part in at most one event, and so did every electron
+    ids_b = [e[2] for e in o.last_events]
+    ids_a = [e[1] for e in o.last_events]
+    assert len(set(ids_b)) == len(ids_b) and len(set(ids_a)) == len(ids_a)
+
+
+def test_cx_rate_and_velocity_swap():
+    cfg = _big_xs(W.small(nx=24, ny=24, nz=24, tip_h=8e-9))
+    o = oracle.Oracle(cfg)
+    rng = np.random.default_rng(13)
+    u = 3.0e6
+    ncell = 10000
+    o.load(_cells_load(cfg, ncell, 1, 2, u * cfg.dt / cfg.h, rng, a="ion"))
+    before = o.state()
+    o.collide(oracle.COLL_MCC2)
+    P = 1 - math.exp(-u * (2 / cfg.h**3) * 6e-19 * cfg.dt)
+    k = len(o.last_events)
+    assert k > 50
+    assert abs(k - ncell * P) < 3.5 * math.sqrt(ncell * P * (1 - P)), (k, ncell * P)
+    after = o.state()
+    vi0 = {int(i): (a, b, c) for i, a, b, c in zip(before[1]["id"], before[1]["vx"], before[1]["vy"], before[1]["vz"])}
+    vn0 = {int(i): (a, b, c) for i, a, b, c in zip(before[2]["id"], before[2]["vx"], before[2]["vy"], before[2]["vz"])}
+    vi1 = {int(i): (a, b, c) for i, a, b, c in zip(after[1]["id"], after[1]["vx"], after[1]["vy"], after[1]["vz"])}
+    vn1 = {int(i): (a, b, c) for i, a, b, c in zip(after[2]["id"], after[2]["vx"], after[2]["vy"], after[2]["vz"])}
+    for kind, ia, ib, _, _ in o.last_events:
+        assert kind == oracle.KIND_CX
+        assert vi1[ia] == vn0[ib] and vn1[ib] == vi0[ia]
+
+
+def test_elastic_conservation_and_isotropy():
+    cfg = _big_xs(W.small(nx=24, ny=24, nz=24, tip_h=8e-9))
+    cfg.xs_iz = np.zeros(256)
+    o = oracle.Oracle(cfg)
+    rng = np.random.default_rng(14)
+    u = 2.0e7
+    o.load(_cells_load(cfg, 6000, 1, 4, u * cfg.dt / cfg.h, rng))
+    before = o.state()
+    o.collide(oracle.COLL_MCC1)
+    after = o.state()
+    me, M = sc.m_e, cfg.m_ion
+
+    def vel(st, s):
+        return {int(i): np.array([a, b, c]) for i, a, b, c in zip(st[s]["id"], st[s]["vx"], st[s]["vy"], st[s]["vz"])}
+
+    e0, e1, n0, n1 = vel(before, 0), vel(after, 0), vel(before, 2), vel(after, 2)
+    cosz = []
+    for kind, ia, ib, _, _ in o.last_events:
+        assert kind == oracle.KIND_ELASTIC
+        p0 = me * e0[ia] + M * n0[ib]
+        p1 = me * e1[ia] + M * n1[ib]
+        np.testing.assert_allclose(p1, p0, rtol=0, atol=1e-12 * me * np.linalg.norm(e0[ia]))
+        k0 = me * e0[ia] @ e0[ia] + M * n0[ib] @ n0[ib]
+        k1 = me * e1[ia] @ e1[ia] + M * n1[ib] @ n1[ib]
+        assert k1 == pytest.approx(k0, rel=1e-12)
+        ur0, ur1 = e0[ia] - n0[ib], e1[ia] - n1[ib]
+        assert np.linalg.norm(ur1) == pytest.approx(np.linalg.norm(ur0), rel=1e-12)
+        cosz.append(ur1 @ ur0 / (ur1 @ ur1))
+    cosz = np.array(cosz)
+    m = len(cosz)
+    assert m > 1000
+    # isotropic scattering: the angle to the old direction has <cos> = 0,
+    # <cos^2> = 1/3
+    assert abs(cosz.mean()) < 3.5 * math.sqrt(1 / 3 / m)
+    assert abs((cosz**2).mean() - 1 / 3) < 3.5 * math.sqrt(4 / 45 / m)
+
+
+def test_impact_ionization_bookkeeping():
+    cfg = _big_xs(W.small(nx=24, ny=24, nz=24, tip_h=8e-9))
+    cfg.xs_el = np.zeros(256)
+    o = oracle.Oracle(cfg)
+    rng = np.random.default_rng(15)
+    u = 2.0e7
+    o.load(_cells_load(cfg, 2000, 1, 4, u * cfg.dt / cfg.h, rng))
+    before = o.state()
+    n0 = [len(s["id"]) for s in before]
+    nid0 = o.next_id
+    o.collide(oracle.COLL_MCC1)
+    after = o.state()
+    k = len(o.last_events)
+    assert k > 100
+    assert [len(s["id"]) for s in after] == [n0[0] + k, n0[1] + k, n0[2] - k]
+    assert o.next_id == nid0 + 2 * k
+    # products are numbered in ascending neutral id order: ion, then electron
+    evs = sorted(o.last_events, key=lambda e: e[2])
+    assert [e[3] for e in evs] == list(range(nid0, nid0 + 2 * k, 2))
+    assert [e[4] for e in evs] == list(range(nid0 + 1, nid0 + 2 * k, 2))
+    me = sc.m_e
+    s = cfg.h / cfg.dt
+
+    def rec(st, sp):
+        return {int(i): (np.array([x, y, z]), np.array([a, b, c]) * s)
+                for i, x, y, z, a, b, c in zip(st[sp]["id"], st[sp]["x"], st[sp]["y"], st[sp]["z"],
+                                              st[sp]["vx"], st[sp]["vy"], st[sp]["vz"])}
+
+    E0, E1, N0, I1 = rec(before, 0), rec(after, 0), rec(before, 2), rec(after, 1)
+    for kind, ie, ineu, nion, ne in o.last_events:
+        assert kind == oracle.KIND_IONIZE
+        xn, vn = N0[ineu]
+        assert np.array_equal(I1[nion][0], xn) and np.allclose(I1[nion][1], vn)
+        assert np.array_equal(E1[ne][0], xn)
+        w0 = E0[ie][1] - vn
+        Ein = 0.5 * me * w0 @ w0 / sc.e
+        w1, w2 = E1[ie][1] - vn, E1[ne][1] - vn
+        Eout = 0.5 * me * (w1 @ w1 + w2 @ w2) / sc.e
+        assert Eout == pytest.approx(Ein - cfg.xi, rel=1e-10)
+
+
+def test_pairing_is_injective_on_crowded_cells():
+    """Cells with many particles of both species: every projectile is paired,
+    no target twice (checked through the event list at P ~ 1)."""
+    cfg = W.small(nx=12, ny=12, nz=12, tip_h=6e-9)
+    cfg.xs_el, cfg.xs_iz, cfg.xs_cx = W.constant_tables(1e-15, 0.0, 0.0)   # P = 1
+    o = oracle.Oracle(cfg)
+    rng = np.random.default_rng(16)
+    o.load(_cells_load(cfg, 40, 7, 11, 0.01, rng))
+    o.collide(oracle.COLL_MCC1)
+    assert len(o.last_events) == 40 * 7
+    b = [e[2] for e in o.last_events]
+    assert len(set(b)) == len(b)
+    o2 = oracle.Oracle(cfg)
+    o2.load(_cells_load(cfg, 40, 11, 7, 0.01, np.random.default_rng(16)))
+    o2.collide(oracle.COLL_MCC1)
+    assert len(o2.last_events) == 40 * 7
+    a = [e[1] for e in o2.last_events]
+    assert len(set(a)) == len(a)
+
+
+def test_field_ionization_rate():
+    """Resting neutrals in a uniform 12 GV/m field ionize at the ADK rate of
+    Eq. dfi: events/step ~ Binomial(N, w dt)."""
+    cfg = W.small(nx=24, ny=24, nz=48, tip_h=8e-9)
+    o = oracle.Oracle(cfg)
+    F = 12e9
+    o.set_phi(np.repeat(np.arange(cfg.nz) * cfg.h * F, cfg.nx * cfg.ny))
+    rng = np.random.default_rng(17)
+    N = 30000
+    pos = np.column_stack([rng.uniform(1, cfg.nx - 2, N), rng.uniform(1, cfg.ny - 2, N), rng.uniform(20, cfg.nz - 3, N)])
+    o.load({"neutral": {"x": pos[:, 0], "y": pos[:, 1], "z": pos[:, 2], "vx": np.zeros(N), "vy": np.zeros(N), "vz": np.zeros(N)}})
+    o.collide(oracle.COLL_FI)
+    p = _adk_atomic_units(F * 1e-9, cfg.xi) * cfg.dt * 1e15
+    k = len(o.last_events)
+    assert abs(k - N * p) < 3.5 * math.sqrt(N * p) + 0.015 * N * p, (k, N * p)
+    assert o.state()[1]["id"].size == k and o.state()[0]["id"].size == k
+    # above the barrier-suppression limit no field ionization is attempted
+    o2 = oracle.Oracle(cfg)
+    o2.set_phi(np.repeat(np.arange(cfg.nz) * cfg.h * 40e9, cfg.nx * cfg.ny))
+    o2.load({"neutral": {"x": pos[:, 0], "y": pos[:, 1], "z": pos[:, 2], "vx": np.zeros(N), "vy": np.zeros(N), "vz": np.zeros(N)}})
+    o2.collide(oracle.COLL_FI)
+    assert len(o2.last_events) == 0 and o2.bsi_skips == N
+
+
+# --------------------------------------------------------------------------
+# Emission
+
+
+def test_emission_patches_cover_tip_surface():
+    cfg = W.tiny()
+    o = oracle.Oracle(cfg)
+    P = o.fn_patches()
+    R, H = cfg.tip_r / cfg.h, cfg.tip_h / cfg.h
+    assert P[:, 6].sum() == pytest.approx(2 * math.pi * R * R + 2 * math.pi * R * (H - R), rel=1e-12)
+    xc = (cfg.nx - 1) / 2
+    zs = np.clip(P[:, 2], 0, H - R)
+    d = np.sqrt((P[:, 0] - xc) ** 2 + (P[:, 1] - xc) ** 2 + (P[:, 2] - zs) ** 2)
+    np.testing.assert_allclose(d, R, rtol=1e-12)
+    np.testing.assert_allclose(np.linalg.norm(P[:, 3:6], axis=1), 1.0, rtol=1e-12)
+
+
+def test_emission_count_statistics():
+    """Over many steps in a fixed field the number of injected electrons
+    matches the expected count sum(J A dt / e) within 3.5 sigma, and every
+    electron starts just outside the tip surface at rest."""
+    cfg = W.tiny()
+    cfg.apex_field = 13e9
+    o = oracle.Oracle(cfg)
+    steps = 300
+    for s in range(steps):
+        o.step_no = s
+        o.inject()
+    assert o.injected > 50
+    assert abs(o.injected - o.n_expected) < 3.5 * math.sqrt(o.n_expected)
+    st = o.state()[0]
+    R, H = cfg.tip_r / cfg.h, cfg.tip_h / cfg.h
+    xc = (cfg.nx - 1) / 2
+    zs = np.clip(st["z"], 0, H - R)
+    d = np.sqrt((st["x"] - xc) ** 2 + (st["y"] - xc) ** 2 + (st["z"] - zs) ** 2)
+    np.testing.assert_allclose(d, R + 1e-3, rtol=1e-9)
+    assert (st["vx"] == 0).all() and (st["vz"] == 0).all()
+    assert np.array_equal(st["id"], np.arange(o.injected, dtype=np.uint32))
+
+
+# --------------------------------------------------------------------------
+# Moments and whole steps
+
+
+def test_shockley_ramo_parallel_plates():
+    """Between parallel plates the weighting field is 1/L, so a charge q
+    moving with v_z induces I = q v_z / L."""
+    cfg = _no_tip()
+    o = oracle.Oracle(cfg)
+    L = (cfg.nz - 1) * cfg.h
+    vz = 2e5
+    o.load({"e": {"x": [4.2], "y": [5.1], "z": [10.3], "vx": [0.0], "vy": [0.0], "vz": [vz * cfg.dt / cfg.h]},
+            "ion": {"x": [4.2], "y": [5.1], "z": [12.0], "vx": [0.0], "vy": [0.0], "vz": [-vz * cfg.dt / cfg.h]}})
+    m = o.moments()
+    assert m["i_sr"] == pytest.approx(2 * sc.e * vz / L, rel=1e-9)   # E0 = -z/L
+    assert m["ke"][0] == pytest.approx(0.5 * sc.m_e * vz * vz, rel=1e-12)
+
+
+def test_step_bookkeeping_and_charge():
+    cfg = W.tiny()
+    o = oracle.Oracle(cfg)
+    o.load(W.initial_load(cfg))
+    loaded = o.next_id
+    o.deposit()
+    o.solve(rtol=1e-8)
+    for _ in range(3):
+        o.step()
+        m = o.moments()
+        ne, ni, nn = m["n"]
+        assert m["q_total"] == 2**40 * (ni - ne)
+        created = int(m["events"][2] + m["events"][4])
+        assert ne + m["absorbed"][0].sum() == 20000 + m["injected"] + created
+        assert ni + m["absorbed"][1].sum() == 200 + created
+        assert nn + m["absorbed"][2].sum() == 2000 - created
+        assert o.next_id == loaded + m["injected"] + 2 * created
