@@ -1,0 +1,219 @@
+/*
+ * pic.h -- C interface of libpic, an MI355X (gfx950) implementation of the
+ * electrostatic particle-in-cell step with Monte Carlo collisions of
+ * "Simulating vacuum arc initiation by coupling emission, heating and plasma
+ * processes" (arXiv 2402.08404, Sec. 2.1-2.3).
+ *
+ * One context holds one instance: a 3D node grid with a grounded cathode plane
+ * carrying a Cu nanotip (cylinder + hemispherical cap, held at 0 V), an anode
+ * plane at V0 and lateral faces with zero normal field (Sec. 2.1, bcf1-bcf3);
+ * three species (electrons, Cu+ ions, Cu neutrals); field emission from the
+ * tip; and a Poisson solve per step (Eq. poi).
+ *
+ * Units of the particle state: positions in grid units X = x/h (node (i,j,k)
+ * at X=i), velocities in grid units per step V = v dt / h. Node fields are
+ * stored as 4 values per node (Ex, Ey, Ez, 0) in V/m. Charge density is an
+ * int64 per node in units of 2^-40 e.
+ *
+ * Memory: every device buffer (particles, grids, scratch) is allocated and
+ * owned by the caller and must outlive the context; the library never frees
+ * them. Host pointers in pic_config are read during pic_init only.
+ *
+ * Threading: a context is bound to one HIP stream and is not thread-safe.
+ * All calls enqueue work on that stream; calls that return host data
+ * (pic_moments, pic_events, pic_solve_poisson, pic_inject) synchronize it.
+ *
+ * Errors: every call returns PIC_OK (0) or a negative pic_status. Device-side
+ * conditions (particle capacity, fixed-point overflow, a cell with more
+ * particles than the collision kernels accept) are sticky: they are raised by
+ * the next synchronizing call and leave the context in a failed state in
+ * which every call returns PIC_E_STATE. pic_last_error gives a message.
+ */
+#ifndef PIC_H
+#define PIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pic_status;
+#define PIC_OK 0
+#define PIC_E_INVALID_ARG (-1)
+#define PIC_E_HIP (-2)
+#define PIC_E_CAPACITY (-3)
+#define PIC_E_OVERFLOW (-4)
+#define PIC_E_NOT_CONVERGED (-5)
+#define PIC_E_STATE (-6)
+
+/* precision of the particle state and of the node field */
+#define PIC_F64 0
+#define PIC_F32 1
+
+/* Poisson solver */
+#define PIC_SOLVER_CG 0      /* plain FP64 conjugate gradients */
+#define PIC_SOLVER_MGCG 1    /* FP64 CG preconditioned by a multigrid V-cycle */
+#define PIC_SOLVER_MIXED 2   /* FP32 inner CG with FP64 dots, FP64 residual refinement */
+
+/* species */
+#define PIC_ELECTRON 0
+#define PIC_ION 1
+#define PIC_NEUTRAL 2
+
+/* initial guess of pic_solve_poisson */
+#define PIC_GUESS_ZERO 0
+#define PIC_GUESS_PREVIOUS 1
+
+/* phases of pic_step; each step runs the selected phases in this order */
+#define PIC_STEP_INJECT 0x01   /* Fowler-Nordheim emission from the tip (Sec. 2.3.1) */
+#define PIC_STEP_PUSH 0x02     /* gather, leapfrog push, boundary removal, deposit, binning (Sec. 2.2) */
+#define PIC_STEP_DEPOSIT 0x04  /* deposit and binning at the current positions, no motion */
+#define PIC_STEP_COLLIDE 0x08  /* MCC (Eqs. colp, du, newv), field ionization (Eq. dfi), products */
+#define PIC_STEP_SOLVE 0x10    /* Poisson solve (Eq. poi) with the previous potential as guess, then the field */
+#define PIC_STEP_FIELD 0x20    /* node field from the current potential only */
+#define PIC_STEP_ADVANCE 0x40  /* advance the step counter */
+#define PIC_STEP_EVENTS 0x80   /* record the collision events of this step (pic_events) */
+#define PIC_STEP_FULL (PIC_STEP_INJECT | PIC_STEP_PUSH | PIC_STEP_COLLIDE | PIC_STEP_SOLVE | PIC_STEP_ADVANCE)
+
+/* event kinds */
+#define PIC_EV_ELASTIC 1   /* e + Cu -> e + Cu */
+#define PIC_EV_IONIZE 2    /* e + Cu -> Cu+ + 2e */
+#define PIC_EV_CX 3        /* Cu+ + Cu -> Cu + Cu+ */
+#define PIC_EV_FIELD_ION 4 /* Cu -> Cu+ + e in the local field */
+
+typedef struct pic_config {
+    int32_t nx, ny, nz;    /* nodes per axis, each >= 4 */
+    int32_t precision;     /* PIC_F64 or PIC_F32 */
+    double h;              /* node spacing [m] */
+    double tip_r;          /* tip radius [m] */
+    double tip_h;          /* total tip height to the apex [m], >= tip_r */
+    double apex_field;     /* requested Laplace field just above the apex [V/m] */
+    double phi_w;          /* work function [eV] */
+    double dt;             /* time step [s] */
+    double xi;             /* first ionization energy of Cu [eV] */
+    double m_ion;          /* Cu mass [kg] */
+    uint64_t seed;         /* Philox4x32-10 key */
+    int32_t xs_n;          /* cross-section table length, >= 2 */
+    int32_t solver;        /* PIC_SOLVER_* used by PIC_STEP_SOLVE */
+    double xs_emin, xs_emax;              /* energies of the first and last table node [eV] */
+    const double* xs_el;                  /* host: e-Cu elastic cross section [m^2] */
+    const double* xs_iz;                  /* host: e-Cu impact ionization [m^2] */
+    const double* xs_cx;                  /* host: Cu+-Cu charge exchange [m^2] */
+    int32_t fn_rings;      /* emission patches: rings on the cap */
+    int32_t fn_az;         /* emission patches: azimuths per ring */
+    double laplace_rtol;   /* tolerance of the unit-anode Laplace solve at init (e.g. 1e-13) */
+    double step_rtol;      /* tolerance of the solve inside pic_step (e.g. 1e-8) */
+    int32_t step_maxit;    /* iteration limit of the solve inside pic_step */
+    int32_t sort_every;    /* reorder particles by cell every this many collide phases (0: never) */
+    int64_t id_capacity;   /* largest particle id + 1 the run may reach (0: 8 x total capacity) */
+} pic_config;
+
+typedef struct pic_buffers {
+    /* per species s: SoA of capacity cap[s]; element type double (PIC_F64)
+     * or float (PIC_F32) */
+    void* x[3];
+    void* y[3];
+    void* z[3];
+    void* vx[3];
+    void* vy[3];
+    void* vz[3];
+    uint32_t* id[3];       /* 0xFFFFFFFF marks a free slot */
+    int64_t cap[3];
+    double* phi;           /* nx*ny*nz potential [V] */
+    double* phi1;          /* nx*ny*nz unit-anode Laplace potential, written by pic_init */
+    int64_t* rho;          /* nx*ny*nz node charge [2^-40 e] */
+    void* field;           /* 4*nx*ny*nz node field [V/m], element type as the particles */
+    void* field0;          /* 4*nx*ny*nz field of phi1 [1/m] (Shockley-Ramo weighting field) */
+    uint8_t* node_type;    /* nx*ny*nz: 0 free, 1 held at 0 V, 2 held at V0 */
+    void* scratch;         /* work memory of pic_scratch_size bytes, 256-byte aligned */
+    size_t scratch_bytes;
+} pic_buffers;
+
+typedef struct pic_particles {
+    int32_t species;       /* PIC_ELECTRON, PIC_ION or PIC_NEUTRAL */
+    int32_t pad;
+    int64_t n;
+    const void *x, *y, *z, *vx, *vy, *vz;  /* device arrays of n elements, same type as the state */
+} pic_particles;
+
+typedef struct pic_solve_info {
+    int32_t iterations;    /* CG iterations (matrix products) */
+    int32_t converged;     /* 1 if ||r|| <= rtol ||b|| was reached */
+    double relres;         /* final ||r|| / ||b|| (recursively updated residual) */
+    double relres0;        /* ||r|| / ||b|| of the initial guess */
+} pic_solve_info;
+
+typedef struct pic_moments_t {
+    int64_t n_alive[3];        /* alive particles per species */
+    int64_t n_slots[3];        /* used slots (alive and free) per species */
+    int64_t absorbed[3][5];    /* cumulative removals by boundary: 1 cathode, 2 anode, 3 lateral, 4 tip */
+    int64_t events[5];         /* cumulative events by kind (PIC_EV_*) */
+    int64_t injected;          /* cumulative emitted electrons */
+    int64_t fn_clamped;        /* cumulative emission patches evaluated with f clamped at 1 */
+    int64_t bsi_count;         /* cumulative neutrals seen above the barrier-suppression field */
+    int64_t q_total;           /* sum of rho [2^-40 e] */
+    int64_t next_id;           /* next particle id to be assigned */
+    int64_t step;              /* step counter */
+    double ke[3];              /* kinetic energy per species [J] */
+    double i_sr;               /* Shockley-Ramo gap current of the stored state [A] */
+    double fn_expected;        /* cumulative expected number of emitted electrons */
+    double v0;                 /* anode potential [V] */
+    double apex_field1;        /* Laplace apex field per volt of anode potential [1/m] */
+    int32_t error;             /* sticky error code, PIC_OK if none */
+    int32_t pad;
+} pic_moments_t;
+
+typedef struct pic_event {
+    int32_t kind;              /* PIC_EV_* */
+    uint32_t id_a;             /* electron (elastic, ionize) or ion (cx); 0xFFFFFFFF for field ionization */
+    uint32_t id_b;             /* the neutral */
+    uint32_t new_ion, new_e;   /* ids of the products (ionize, field ionization), else 0xFFFFFFFF */
+} pic_event;
+
+typedef struct pic_ctx pic_ctx;
+
+/* Bytes of work memory pic_init needs for this configuration and these
+ * capacities (cap[3] particles per species). */
+pic_status pic_scratch_size(const pic_config* cfg, const int64_t cap[3], size_t* bytes);
+
+/* Create a context. Validates cfg (INVALID_ARG), computes the node types,
+ * solves the unit-anode Laplace problem to cfg->laplace_rtol (phi1, field0),
+ * sets V0 = apex_field / (Laplace apex field per volt), phi = V0 phi1 and the
+ * node field, and empties all species. Synchronizes the stream. */
+pic_status pic_init(const pic_config* cfg, const pic_buffers* bufs, void* hip_stream, pic_ctx** out);
+
+/* With src != NULL: append src->n particles of one species (copied from
+ * device memory), numbering them from the next id in array order.
+ * With src == NULL: Fowler-Nordheim emission for the current step (as
+ * PIC_STEP_INJECT). n_added (optional) receives the number appended; the call
+ * synchronizes. Errors: INVALID_ARG, CAPACITY. */
+pic_status pic_inject(pic_ctx* ctx, const pic_particles* src, int64_t* n_added);
+
+/* Run nsteps steps of the phases selected in flags (PIC_STEP_*). The
+ * work is enqueued on the stream; only the solve phase synchronizes (to test
+ * convergence). */
+pic_status pic_step(pic_ctx* ctx, int32_t nsteps, uint32_t flags);
+
+/* Solve Eq. poi for the charge in rho with the given solver and guess until
+ * ||b - A phi|| <= rtol ||b|| or maxit iterations, then compute the node field.
+ * Returns NOT_CONVERGED (context stays usable) when maxit is reached. */
+pic_status pic_solve_poisson(pic_ctx* ctx, int32_t solver, int32_t guess, double rtol, int32_t maxit,
+                             pic_solve_info* info);
+
+/* Reductions over the current state; synchronizes and reports sticky
+ * device errors. */
+pic_status pic_moments(pic_ctx* ctx, pic_moments_t* out);
+
+/* Copy up to cap events of the last collide phase run with PIC_STEP_EVENTS;
+ * n receives the number recorded. */
+pic_status pic_events(pic_ctx* ctx, pic_event* out, int64_t cap, int64_t* n);
+
+const char* pic_last_error(const pic_ctx* ctx);
+void pic_destroy(pic_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -724,11 +724,11 @@ int orc_collide(const orc_config* c, uint32_t step, int32_t flags, const double*
         double ebsi = 1.5 * pow(c->xi, 1.5);
         double dt_fs = c->dt * 1e15;
         for (int64_t p = 0; p < N->n; ++p) {
-            if (used[ORC_SP_NEU][p]) continue;
             double e[3];
             orc_gather(c, E, N->x[p], N->y[p], N->z[p], e);
             double Eg = sqrt(e[0] * e[0] + e[1] * e[1] + e[2] * e[2]) * 1e-9;
-            if (Eg > ebsi) { o->n_bsi_skip++; continue; }
+            if (Eg > ebsi) { o->n_bsi_skip++; continue; }  /* counted for every neutral */
+            if (used[ORC_SP_NEU][p]) continue;
             double pdt = orc_adk_rate(c, Eg) * dt_fs;
             double U, unused;
             draw2(c, N->id[p], step, TAG_FI, 0, &U, &unused);

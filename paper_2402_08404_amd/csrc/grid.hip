@@ -1,0 +1,500 @@
+// grid.hip -- node-grid kernels: node types, node field, prefix scan, and the
+// FP64 conjugate-gradient Poisson solver.
+//
+// Poisson's equation (Sec. 2.1, Eq. poi with boundary conditions bcf1-bcf3) is
+// discretized by finite volumes on node control volumes clipped at the lateral
+// faces: for a free node i, sum_j f_ij (phi_i - phi_j) = q_i / (eps0 h), with
+// f_ij = 1 inside, 1/2 on a lateral face and 1/4 on a lateral edge. The
+// operator is applied matrix-free from the node types.
+#include "pic_internal.hpp"
+
+namespace pic {
+
+__global__ void k_node_types(Grid g, uint8_t* type) {
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.nn) return;
+    int i = (int)(n % g.nx);
+    int j = (int)((n / g.nx) % g.ny);
+    int k = (int)(n / ((int64_t)g.nx * g.ny));
+    uint8_t t = 0;
+    if (k == 0) t = 1;
+    else if (k == g.nz - 1) t = 2;
+    else if (inside_tip(g, (double)i, (double)j, (double)k)) t = 1;
+    type[n] = t;
+}
+
+hipError_t launch_node_types(pic_ctx* c) {
+    int64_t G = (c->g.nn + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_node_types, dim3((unsigned)G), dim3(kBlock), 0, c->stream, c->g, c->buf.node_type);
+    return hipGetLastError();
+}
+
+// Node field E = -grad phi [V/m]: central differences inside, zero normal
+// component on the lateral faces (bcf2), one-sided on the two Dirichlet planes.
+template <typename T>
+__global__ void k_field(Grid g, const double* __restrict__ phi, typename V4<T>::type* __restrict__ E) {
+    int64_t G = gridDim.x;
+    int64_t n = xcd_block(blockIdx.x, G) * blockDim.x + threadIdx.x;
+    if (n >= g.nn) return;
+    int i = (int)(n % g.nx);
+    int j = (int)((n / g.nx) % g.ny);
+    int k = (int)(n / ((int64_t)g.nx * g.ny));
+    int64_t pl = (int64_t)g.nx * g.ny;
+    double ex = 0.0, ey = 0.0, ez;
+    if (i > 0 && i < g.nx - 1) ex = -(phi[n + 1] - phi[n - 1]) / (2.0 * g.h);
+    if (j > 0 && j < g.ny - 1) ey = -(phi[n + g.nx] - phi[n - g.nx]) / (2.0 * g.h);
+    if (k == 0) ez = -(phi[n + pl] - phi[n]) / g.h;
+    else if (k == g.nz - 1) ez = -(phi[n] - phi[n - pl]) / g.h;
+    else ez = -(phi[n + pl] - phi[n - pl]) / (2.0 * g.h);
+    typename V4<T>::type v;
+    v.x = (T)ex;
+    v.y = (T)ey;
+    v.z = (T)ez;
+    v.w = (T)0;
+    E[n] = v;
+}
+
+hipError_t launch_field(pic_ctx* c, const double* phi, void* field) {
+    int64_t G = (c->g.nn + kBlock - 1) / kBlock;
+    if (c->cfg.precision == PIC_F32)
+        hipLaunchKernelGGL(k_field<float>, dim3((unsigned)G), dim3(kBlock), 0, c->stream, c->g, phi,
+                           (float4*)field);
+    else
+        hipLaunchKernelGGL(k_field<double>, dim3((unsigned)G), dim3(kBlock), 0, c->stream, c->g, phi,
+                           (double4*)field);
+    return hipGetLastError();
+}
+
+__global__ void k_zero(uint4* p, int64_t n16, uint8_t* tail, int64_t ntail) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t s = (int64_t)gridDim.x * blockDim.x;
+    for (; i < n16; i += s) p[i] = make_uint4(0, 0, 0, 0);
+    if (blockIdx.x == 0 && threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+// Zero device memory with a kernel (no memset nodes, so the work can be
+// captured in a graph).
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    int64_t n16 = (int64_t)(bytes / 16);
+    int64_t ntail = (int64_t)(bytes % 16);
+    int64_t G = (n16 + kBlock - 1) / kBlock;
+    if (G > 16384) G = 16384;
+    if (G < 1) G = 1;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)G), dim3(kBlock), 0, s, (uint4*)p, n16,
+                       (uint8_t*)p + n16 * 16, ntail);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive prefix scan of uint32 (or of popcounts of uint32 words):
+// per-tile reduction, scan of the tile sums in one block, per-tile scan.
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;
+
+template <bool POP>
+__device__ inline uint32_t scan_in(const uint32_t* in, int64_t i, int64_t n) {
+    if (i >= n) return 0u;
+    uint32_t v = in[i];
+    return POP ? (uint32_t)__popc(v) : v;
+}
+
+__device__ inline int64_t scan_len(int64_t n, const uint32_t* nd) {
+    if (!nd) return n;
+    int64_t d = (int64_t)*nd;
+    return d < n ? d : n;
+}
+
+template <bool POP>
+__global__ void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n, const uint32_t* nd,
+                              uint32_t* __restrict__ bsum) {
+    __shared__ uint32_t sh[kBlock / 64];
+    n = scan_len(n, nd);
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) s += scan_in<POP>(in, base + k * kBlock + threadIdx.x, n);
+    uint32_t t = block_sum(s, sh);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = t;
+}
+
+// Exclusive scan of the tile sums in one block (any count); writes the total.
+__global__ void k_scan_top(uint32_t* bsum, int64_t nb, uint32_t* total) {
+    __shared__ uint32_t sh[kBlock];
+    uint32_t carry = 0;
+    for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
+        int64_t i = b0 + threadIdx.x;
+        uint32_t v = i < nb ? bsum[i] : 0u;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int o = 1; o < kBlock; o <<= 1) {
+            uint32_t add = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0u;
+            __syncthreads();
+            sh[threadIdx.x] += add;
+            __syncthreads();
+        }
+        uint32_t incl = sh[threadIdx.x];
+        if (i < nb) bsum[i] = carry + incl - v;
+        uint32_t last = sh[kBlock - 1];
+        __syncthreads();
+        carry += last;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+template <bool POP>
+__global__ void k_scan_down(uint32_t* __restrict__ in, int64_t n, const uint32_t* nd,
+                            const uint32_t* __restrict__ bsum, uint32_t* __restrict__ out, int zero_in) {
+    __shared__ uint32_t tile[kScanTile];
+    __shared__ uint32_t sh[kBlock];
+    n = scan_len(n, nd);
+    if ((int64_t)blockIdx.x * kScanTile >= n) return;
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k * kBlock + threadIdx.x;
+        tile[k * kBlock + threadIdx.x] = scan_in<POP>(in, i, n);
+        if (zero_in && i < n) in[i] = 0u;
+    }
+    __syncthreads();
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) s += tile[threadIdx.x * kScanItems + k];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 1; o < kBlock; o <<= 1) {
+        uint32_t add = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0u;
+        __syncthreads();
+        sh[threadIdx.x] += add;
+        __syncthreads();
+    }
+    uint32_t run = bsum[blockIdx.x] + sh[threadIdx.x] - s;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        uint32_t v = tile[threadIdx.x * kScanItems + k];
+        tile[threadIdx.x * kScanItems + k] = run;
+        run += v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k * kBlock + threadIdx.x;
+        if (i < n) out[i] = tile[k * kBlock + threadIdx.x];
+    }
+}
+
+// out[i] = sum of in[0..i) for i < n and *total = sum of all, where n is
+// n_max or, when nd is given, min(n_max, *nd) read on the device. With
+// zero_in the input is cleared in the same pass (in and out may not alias).
+hipError_t scan_u32(pic_ctx* c, const uint32_t* in, uint32_t* out, int64_t n_max, const uint32_t* nd,
+                    uint32_t* total, bool zero_in, bool popcount) {
+    int64_t nb = (n_max + kScanTile - 1) / kScanTile;
+    if (nb < 1) nb = 1;
+    if (nb > c->scan_blocks_n) return hipErrorInvalidValue;
+    if (popcount)
+        hipLaunchKernelGGL(k_scan_reduce<true>, dim3((unsigned)nb), dim3(kBlock), 0, c->stream, in, n_max, nd,
+                           c->scan_blocks);
+    else
+        hipLaunchKernelGGL(k_scan_reduce<false>, dim3((unsigned)nb), dim3(kBlock), 0, c->stream, in, n_max, nd,
+                           c->scan_blocks);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, c->stream, c->scan_blocks, nb, total);
+    if (popcount)
+        hipLaunchKernelGGL(k_scan_down<true>, dim3((unsigned)nb), dim3(kBlock), 0, c->stream, (uint32_t*)in, n_max,
+                           nd, c->scan_blocks, out, zero_in ? 1 : 0);
+    else
+        hipLaunchKernelGGL(k_scan_down<false>, dim3((unsigned)nb), dim3(kBlock), 0, c->stream, (uint32_t*)in,
+                           n_max, nd, c->scan_blocks, out, zero_in ? 1 : 0);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Conjugate gradients. Two fused kernels per iteration; the scalars live on
+// the device and each reduction is finished by the last block to arrive,
+// summing the block partials in index order (deterministic). Kernels return
+// at once when the solve is done, so the host can enqueue iterations in
+// chunks and test convergence once per chunk.
+
+struct CgArgs {
+    Grid g;
+    const uint8_t* type;
+    double* x;
+    double* r;
+    const double* p_old;
+    double* p_new;
+    double* q;
+    const int64_t* rho;
+    double qscale;   // 2^-40 e / (eps0 h)
+    double V0;
+    DevState* s;
+    double* partials;
+};
+
+__device__ inline double half_at_edge(int i, int n) { return (i == 0 || i == n - 1) ? 0.5 : 1.0; }
+
+// Last-block reduction of per-block partials; returns true in the one thread
+// that holds the total in *tot.
+__device__ inline bool finish_sum(double v, double* partials, unsigned int* counter, double* tot) {
+    __shared__ double sh[kBlock / 64];
+    __shared__ int last;
+    double b = block_sum(v, sh);
+    if (threadIdx.x == 0) {
+        partials[blockIdx.x] = b;
+        __threadfence();
+        unsigned int prev = atomicAdd(counter, 1u);
+        last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < gridDim.x; i += blockDim.x) s += ((volatile double*)partials)[i];
+    double t = block_sum(s, sh);  // fixed order: strided per thread, then tree
+    if (threadIdx.x == 0) {
+        *counter = 0u;
+        *tot = t;
+    }
+    return threadIdx.x == 0;
+}
+
+__device__ inline void node_ijk(const Grid& g, int64_t n, int& i, int& j, int& k) {
+    i = (int)(n % g.nx);
+    j = (int)((n / g.nx) % g.ny);
+    k = (int)(n / ((int64_t)g.nx * g.ny));
+}
+
+// Dirichlet values into phi, optional zero guess, p_new cleared.
+__global__ void k_cg_init(CgArgs a, int zero_guess) {
+    const Grid& g = a.g;
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.nn) return;
+    uint8_t t = a.type[n];
+    if (t != 0) {
+        a.x[n] = (t == 2) ? a.V0 : 0.0;
+        a.r[n] = 0.0;
+    } else if (zero_guess) {
+        a.x[n] = 0.0;
+    }
+    a.p_new[n] = 0.0;
+}
+
+// r = q/(eps0 h) - L(phi) with the Dirichlet values in phi, and the norms of
+// r and of b = q/(eps0 h) + Dirichlet lifts.
+__global__ void k_cg_resid(CgArgs a) {
+    const Grid& g = a.g;
+    int64_t n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    double bb = 0.0, rr = 0.0;
+    if (n < g.nn && a.type[n] == 0) {
+        int i, j, k;
+        node_ijk(g, n, i, j, k);
+        int64_t pl = (int64_t)g.nx * g.ny;
+        double fx = half_at_edge(j, g.ny) * half_at_edge(k, g.nz);
+        double fy = half_at_edge(i, g.nx) * half_at_edge(k, g.nz);
+        double fz = half_at_edge(i, g.nx) * half_at_edge(j, g.ny);
+        double xi = a.x[n];
+        double qv = (double)a.rho[n] * a.qscale;
+        double b = qv, lx = 0.0;
+        int64_t nb[6] = {n - 1, n + 1, n - g.nx, n + g.nx, n - pl, n + pl};
+        bool has[6] = {i > 0, i < g.nx - 1, j > 0, j < g.ny - 1, true, true};
+        double f[6] = {fx, fx, fy, fy, fz, fz};
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            if (!has[d]) continue;
+            double xj = a.x[nb[d]];
+            lx += f[d] * (xi - xj);
+            if (a.type[nb[d]] != 0) b += f[d] * xj;
+        }
+        double r = qv - lx;
+        a.r[n] = r;
+        bb = b * b;
+        rr = r * r;
+    }
+    // two reductions: b.b then r.r, both finished by the last block
+    __shared__ double sh[kBlock / 64];
+    __shared__ int last;
+    double sb = block_sum(bb, sh);
+    double sr = block_sum(rr, sh);
+    if (threadIdx.x == 0) {
+        a.partials[2 * blockIdx.x] = sb;
+        a.partials[2 * blockIdx.x + 1] = sr;
+        __threadfence();
+        unsigned int prev = atomicAdd(&a.s->red_count, 1u);
+        last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    double tb = 0.0, tr = 0.0;
+    for (int64_t q = threadIdx.x; q < gridDim.x; q += blockDim.x) {
+        tb += ((volatile double*)a.partials)[2 * q];
+        tr += ((volatile double*)a.partials)[2 * q + 1];
+    }
+    tb = block_sum(tb, sh);
+    tr = block_sum(tr, sh);
+    if (threadIdx.x == 0) {
+        DevState* s = a.s;
+        s->red_count = 0u;
+        s->bb = tb;
+        s->rr = tr;
+        s->rr0 = tr;
+        s->beta = 0.0;
+        s->it = 0;
+        s->zero_solution = (tb == 0.0);
+        s->done = (tb == 0.0) || (sqrt(tr) <= s->rtol * sqrt(tb)) || (s->maxit <= 0);
+    }
+}
+
+// p_new = r + beta p_old, q = A p_new, partial p_new . q; alpha = rr / pq.
+__global__ void k_cg_a(CgArgs a) {
+    DevState* s = a.s;
+    if (s->done) return;
+    const Grid& g = a.g;
+    double beta = s->beta;
+    int64_t n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    double pq = 0.0;
+    if (n < g.nn) {
+        if (a.type[n] != 0) {
+            a.p_new[n] = 0.0;
+            a.q[n] = 0.0;
+        } else {
+            int i, j, k;
+            node_ijk(g, n, i, j, k);
+            int64_t pl = (int64_t)g.nx * g.ny;
+            double fx = half_at_edge(j, g.ny) * half_at_edge(k, g.nz);
+            double fy = half_at_edge(i, g.nx) * half_at_edge(k, g.nz);
+            double fz = half_at_edge(i, g.nx) * half_at_edge(j, g.ny);
+            double pi = a.r[n] + beta * a.p_old[n];
+            double acc = 0.0;
+            int64_t nb[6] = {n - 1, n + 1, n - g.nx, n + g.nx, n - pl, n + pl};
+            bool has[6] = {i > 0, i < g.nx - 1, j > 0, j < g.ny - 1, true, true};
+            double f[6] = {fx, fx, fy, fy, fz, fz};
+#pragma unroll
+            for (int d = 0; d < 6; ++d) {
+                if (!has[d]) continue;
+                int64_t m = nb[d];
+                double pj = (a.type[m] == 0) ? a.r[m] + beta * a.p_old[m] : 0.0;
+                acc += f[d] * (pi - pj);
+            }
+            a.p_new[n] = pi;
+            a.q[n] = acc;
+            pq = pi * acc;
+        }
+    }
+    double tot;
+    if (finish_sum(pq, a.partials, &s->red_count, &tot)) {
+        s->pq = tot;
+        s->alpha = s->rr / tot;
+    }
+}
+
+// x += alpha p, r -= alpha q, partial r.r; beta, convergence test.
+__global__ void k_cg_b(CgArgs a) {
+    DevState* s = a.s;
+    if (s->done) return;
+    const Grid& g = a.g;
+    double alpha = s->alpha;
+    int64_t n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    double rr = 0.0;
+    if (n < g.nn && a.type[n] == 0) {
+        double p = a.p_new[n];
+        a.x[n] += alpha * p;
+        double r = a.r[n] - alpha * a.q[n];
+        a.r[n] = r;
+        rr = r * r;
+    }
+    double tot;
+    if (finish_sum(rr, a.partials, &s->red_count, &tot)) {
+        s->beta = tot / s->rr;
+        s->rr = tot;
+        s->it += 1;
+        s->done = (sqrt(tot) <= s->rtol * sqrt(s->bb)) || (s->it >= s->maxit);
+    }
+}
+
+__global__ void k_cg_zero_free(Grid g, const uint8_t* type, double* x, const DevState* s) {
+    if (!s->zero_solution) return;
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < g.nn && type[n] == 0) x[n] = 0.0;
+}
+
+__global__ void k_cg_setup(DevState* s, double rtol, int maxit) {
+    s->rtol = rtol;
+    s->maxit = maxit;
+    s->done = 0;
+    s->red_count = 0u;
+}
+
+int cg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess, double rtol, int maxit,
+             pic_solve_info* info) {
+    const Grid& g = c->g;
+    int64_t G = (g.nn + kBlock - 1) / kBlock;
+    CgArgs a;
+    a.g = g;
+    a.type = c->buf.node_type;
+    a.x = phi;
+    a.r = c->cg_r;
+    a.p_old = c->cg_p0;
+    a.p_new = c->cg_p1;
+    a.q = c->cg_q;
+    a.rho = rho;
+    a.qscale = ldexp(1.0, -40) * kQe / (kEps0 * g.h);
+    a.V0 = V0;
+    a.s = c->st;
+    a.partials = c->partials;
+    hipLaunchKernelGGL(k_cg_setup, dim3(1), dim3(1), 0, c->stream, c->st, rtol, maxit);
+    hipLaunchKernelGGL(k_cg_init, dim3((unsigned)G), dim3(kBlock), 0, c->stream, a, guess == PIC_GUESS_ZERO);
+    // p_old must read as zero in the first iteration (beta = 0 and p_old = r
+    // would also do; zero is cleaner)
+    (void)launch_zero(c->cg_p0, sizeof(double) * g.nn, c->stream);
+    hipLaunchKernelGGL(k_cg_resid, dim3((unsigned)G), dim3(kBlock), 0, c->stream, a);
+    double* pa = c->cg_p0;
+    double* pb = c->cg_p1;
+    int chunk = 8;
+    int launched = 0;
+    while (true) {
+        for (int t = 0; t < chunk && launched < maxit; ++t, ++launched) {
+            a.p_old = pa;
+            a.p_new = pb;
+            hipLaunchKernelGGL(k_cg_a, dim3((unsigned)G), dim3(kBlock), 0, c->stream, a);
+            hipLaunchKernelGGL(k_cg_b, dim3((unsigned)G), dim3(kBlock), 0, c->stream, a);
+            double* t2 = pa;
+            pa = pb;
+            pb = t2;
+        }
+        (void)hipMemcpyAsync(c->host_st, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream);
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return -2;
+        if (c->host_st->done || launched >= maxit) break;
+        if (chunk < 64) chunk *= 2;
+    }
+    hipLaunchKernelGGL(k_cg_zero_free, dim3((unsigned)G), dim3(kBlock), 0, c->stream, g, c->buf.node_type, phi,
+                       c->st);
+    (void)hipMemcpyAsync(c->host_st, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return -2;
+    const DevState* h = c->host_st;
+    double bn = sqrt(h->bb);
+    info->iterations = h->it;
+    info->relres = h->zero_solution ? 0.0 : sqrt(h->rr) / bn;
+    info->relres0 = h->zero_solution ? 0.0 : sqrt(h->rr0) / bn;
+    info->converged = h->zero_solution || (sqrt(h->rr) <= rtol * bn);
+    return 0;
+}
+
+// Potential at a point by trilinear interpolation (one thread).
+__global__ void k_interp(Grid g, const double* phi, double X, double Y, double Z, double* out) {
+    int i = clampi((int)floor(X), 0, g.nx - 2), j = clampi((int)floor(Y), 0, g.ny - 2),
+        k = clampi((int)floor(Z), 0, g.nz - 2);
+    double fx = X - i, fy = Y - j, fz = Z - k;
+    double s = 0.0;
+    for (int t = 0; t < 8; ++t) {
+        double w = ((t & 1) ? fx : 1.0 - fx) * ((t & 2) ? fy : 1.0 - fy) * ((t & 4) ? fz : 1.0 - fz);
+        int64_t m = ((int64_t)(k + ((t >> 2) & 1)) * g.ny + j + ((t >> 1) & 1)) * g.nx + i + (t & 1);
+        s += w * phi[m];
+    }
+    *out = s;
+}
+
+hipError_t apex_interp(pic_ctx* c, const double* phi, double X, double Y, double Z, double* out_dev) {
+    hipLaunchKernelGGL(k_interp, dim3(1), dim3(1), 0, c->stream, c->g, phi, X, Y, Z, out_dev);
+    return hipGetLastError();
+}
+
+}  // namespace pic

@@ -1,0 +1,1245 @@
+// particles.hip -- particle kernels of one PIC-MCC step: push with deposit and
+// binning, cell bins, Monte Carlo collisions, field ionization, products,
+// reordering by cell, field emission, explicit loads.
+#include "pic_internal.hpp"
+
+namespace pic {
+
+// ---------------------------------------------------------------------------
+// Push (Sec. 2.2): gather of the node field at x^n by trilinear weights,
+// leapfrog kick v^{n+1/2} = v^{n-1/2} + (q/m) E dt and drift
+// x^{n+1} = x^n + v^{n+1/2} dt (neutrals drift); particles that end outside
+// the vacuum region are removed. Fused with the rest of the per-particle pass
+// over x^{n+1}:
+//  - the charge deposit (source of Eq. poi): CIC weights quantized per axis to
+//    2^-13, 2^-13, 2^-14 so each product is an integer number of 2^-40 e,
+//    accumulated with int64 atomics (order independent, hence deterministic);
+//  - the cell key and the particle's slot among the particles of its cell;
+//  - for neutrals, the field-ionization test of Eq. dfi at x^{n+1} (the draw
+//    is keyed by particle id and step, so the test can run here; whether the
+//    neutral is free to ionize is decided after the collisions);
+//  - the largest speed per species (bound for the null-collision test).
+// Products of ionization carry +e and -e at the same point, so depositing
+// before the collisions gives the same node charge as after them.
+
+template <typename T>
+struct PushArgs {
+    Species<T> s;
+    const typename V4<T>::type* field;
+    Grid g;
+    T kq;
+    int64_t* rho;
+    int64_t sign;
+    uint32_t* cnt;
+    uint32_t* key;
+    uint32_t* slot;
+    DevState* st;
+    uint32_t step;
+    uint64_t seed;
+    uint32_t* fi_list;
+    double fi_thr, ebsi, adk_c, adk_e, x32, dt_fs;
+};
+
+template <typename T>
+__device__ inline void gather(const Grid& g, const typename V4<T>::type* __restrict__ E, T X, T Y, T Z, T& ex,
+                              T& ey, T& ez) {
+    int i = clampi((int)floor(X), 0, g.nx - 2);
+    int j = clampi((int)floor(Y), 0, g.ny - 2);
+    int k = clampi((int)floor(Z), 0, g.nz - 2);
+    T fx = X - (T)i, fy = Y - (T)j, fz = Z - (T)k;
+    T gx = (T)1 - fx, gy = (T)1 - fy, gz = (T)1 - fz;
+    int64_t n0 = ((int64_t)k * g.ny + j) * g.nx + i;
+    int64_t pl = (int64_t)g.nx * g.ny;
+    auto e000 = E[n0], e100 = E[n0 + 1], e010 = E[n0 + g.nx], e110 = E[n0 + g.nx + 1];
+    auto e001 = E[n0 + pl], e101 = E[n0 + pl + 1], e011 = E[n0 + pl + g.nx], e111 = E[n0 + pl + g.nx + 1];
+    T w000 = gx * gy * gz, w100 = fx * gy * gz, w010 = gx * fy * gz, w110 = fx * fy * gz;
+    T w001 = gx * gy * fz, w101 = fx * gy * fz, w011 = gx * fy * fz, w111 = fx * fy * fz;
+    ex = w000 * e000.x + w100 * e100.x + w010 * e010.x + w110 * e110.x + w001 * e001.x + w101 * e101.x +
+         w011 * e011.x + w111 * e111.x;
+    ey = w000 * e000.y + w100 * e100.y + w010 * e010.y + w110 * e110.y + w001 * e001.y + w101 * e101.y +
+         w011 * e011.y + w111 * e111.y;
+    ez = w000 * e000.z + w100 * e100.z + w010 * e010.z + w110 * e110.z + w001 * e001.z + w101 * e101.z +
+         w011 * e011.z + w111 * e111.z;
+}
+
+__device__ inline unsigned int speed_bits(double s) {
+    float f = (float)s;
+    if ((double)f < s) f = __uint_as_float(__float_as_uint(f) + 1u);  // next float up (s >= 0)
+    return __float_as_uint(f);
+}
+
+template <typename T, int SP, bool MOVE>
+__global__ __launch_bounds__(kBlock) void k_push(PushArgs<T> a) {
+    const Grid& g = a.g;
+    const int64_t n = (int64_t)a.st->n_slots[SP];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    unsigned int smax = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint32_t id = a.s.id[i];
+        if (id == kDead) {
+            a.key[i] = kDead;
+            continue;
+        }
+        T X = a.s.x[i], Y = a.s.y[i], Z = a.s.z[i];
+        T VX = a.s.vx[i], VY = a.s.vy[i], VZ = a.s.vz[i];
+        if (MOVE) {
+            if (SP != PIC_NEUTRAL) {
+                T ex, ey, ez;
+                gather<T>(g, a.field, X, Y, Z, ex, ey, ez);
+                VX += a.kq * ex;
+                VY += a.kq * ey;
+                VZ += a.kq * ez;
+                a.s.vx[i] = VX;
+                a.s.vy[i] = VY;
+                a.s.vz[i] = VZ;
+            }
+            X += VX;
+            Y += VY;
+            Z += VZ;
+            a.s.x[i] = X;
+            a.s.y[i] = Y;
+            a.s.z[i] = Z;
+        }
+        double Xd = (double)X, Yd = (double)Y, Zd = (double)Z;
+        int code = boundary_code(g, Xd, Yd, Zd);
+        if (code != 0) {
+            a.s.id[i] = kDead;
+            a.key[i] = kDead;
+            atomicAdd(&a.st->absorbed[SP][code], 1ull);
+            continue;
+        }
+        int ci = clampi((int)floor(Xd), 0, g.nx - 2);
+        int cj = clampi((int)floor(Yd), 0, g.ny - 2);
+        int ck = clampi((int)floor(Zd), 0, g.nz - 2);
+        uint32_t cell = (uint32_t)(((int64_t)ck * (g.ny - 1) + cj) * (g.nx - 1) + ci);
+        a.key[i] = cell;
+        a.slot[i] = atomicAdd(&a.cnt[cell], 1u);
+        double vx = (double)VX, vy = (double)VY, vz = (double)VZ;
+        unsigned int sb = speed_bits(sqrt(vx * vx + vy * vy + vz * vz));
+        smax = sb > smax ? sb : smax;
+        if (SP != PIC_NEUTRAL) {
+            int64_t qx = quantize(Xd - ci, 13), qy = quantize(Yd - cj, 13), qz = quantize(Zd - ck, 14);
+            int64_t wx0 = 8192 - qx, wy0 = 8192 - qy, wz0 = 16384 - qz;
+            int64_t n0 = ((int64_t)ck * g.ny + cj) * g.nx + ci;
+            int64_t pl = (int64_t)g.nx * g.ny;
+            unsigned long long* q = (unsigned long long*)a.rho;
+            int64_t s = a.sign;
+            atomicAdd(q + n0, (unsigned long long)(s * wx0 * wy0 * wz0));
+            atomicAdd(q + n0 + 1, (unsigned long long)(s * qx * wy0 * wz0));
+            atomicAdd(q + n0 + g.nx, (unsigned long long)(s * wx0 * qy * wz0));
+            atomicAdd(q + n0 + g.nx + 1, (unsigned long long)(s * qx * qy * wz0));
+            atomicAdd(q + n0 + pl, (unsigned long long)(s * wx0 * wy0 * qz));
+            atomicAdd(q + n0 + pl + 1, (unsigned long long)(s * qx * wy0 * qz));
+            atomicAdd(q + n0 + pl + g.nx, (unsigned long long)(s * wx0 * qy * qz));
+            atomicAdd(q + n0 + pl + g.nx + 1, (unsigned long long)(s * qx * qy * qz));
+        } else {
+            // Field ionization of Eq. dfi: rate per fs at the local field in
+            // GV/m; no attempt above the barrier-suppression field.
+            T ex, ey, ez;
+            gather<T>(g, a.field, X, Y, Z, ex, ey, ez);
+            double exd = (double)ex, eyd = (double)ey, ezd = (double)ez;
+            double Eg = sqrt(exd * exd + eyd * eyd + ezd * ezd) * 1e-9;
+            if (Eg > a.ebsi) {
+                atomicAdd(&a.st->bsi_count, 1ull);
+            } else if (Eg > a.fi_thr) {
+                double pdt = a.adk_c * pow(20.5 * a.x32 / Eg, a.adk_e) * exp(-6.83 * a.x32 / Eg) * a.dt_fs;
+                Draw2 u = draw2(a.seed, id, a.step, kTagFi, 0);
+                if (pdt > u.a) {
+                    unsigned long long p = atomicAdd(&a.st->n_fi, 1ull);
+                    a.fi_list[p] = (uint32_t)i;
+                }
+            }
+        }
+    }
+    // largest speed of the species
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned int v = __shfl_xor(smax, o, 64);
+        smax = v > smax ? v : smax;
+    }
+    if (lane_id() == 0 && smax) atomicMax(&a.st->smax_bits[SP], smax);
+}
+
+// ---------------------------------------------------------------------------
+// Cell bins: bins[off[cell] + slot] = species << 30 | index.
+
+__global__ void k_scatter(int sp, const uint32_t* __restrict__ key, const uint32_t* __restrict__ slot,
+                          const uint32_t* __restrict__ off, uint32_t* __restrict__ bins, const DevState* st) {
+    int64_t n = (int64_t)st->n_push[sp];
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint32_t k = key[i];
+        if (k == kDead) continue;
+        bins[off[k] + slot[i]] = ((uint32_t)sp << 30) | (uint32_t)i;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Monte Carlo collisions (Sec. 2.2, Eqs. colp, du, newv; Table colls).
+// Per cell and pair class -- (e, Cu) with elastic scattering and impact
+// ionization, then (Cu+, Cu) with charge exchange -- the species with fewer
+// particles in the cell is the projectile (tie: the charged one); projectiles
+// in ascending id order take targets in ascending id order, cyclically
+// shifted by floor(U_c N_t) with U_c drawn per cell, so no target is used
+// twice; n is the target count over the cell volume. A pair collides when
+// U1 < P = 1 - exp(-u n sigma_tot dt); U2 picks the process in proportion to
+// its cross section. A particle has at most one event per step: a neutral
+// with an (e, Cu) event keeps its place in the (Cu+, Cu) pairing but its pair
+// is void. Null-collision test: with u bounded by the sum of the largest
+// speeds of the two species and sigma_tot by the table maximum, U1 >= P_null
+// rules out a collision before any velocity is read.
+
+template <typename T>
+struct MccArgs {
+    Species<T> sp[3];
+    const uint32_t* off;
+    uint32_t* bins;
+    int64_t nc;
+    uint32_t* big;
+    DevState* st;
+    uint32_t step;
+    uint64_t seed;
+    double h, dt, m_ion, xi;
+    const double* xs;   // el, iz, cx tables
+    int xs_n;
+    double xs_emin, xs_lnr;
+    double xs_max[2];
+    uint32_t* nflag;
+    uint32_t* bitmap_imp;
+    uint32_t* prod_list;
+    double* prod_ve;
+    int32_t* prod_ev;
+    pic_event* ev;
+    int64_t ev_cap;
+    int record, write_sorted;
+};
+
+__device__ inline double xs_lookup(const double* tab, int n, double emin, double lnr, double E) {
+    if (E <= emin) return tab[0];
+    double emax = emin * exp(lnr);
+    if (E >= emax) return tab[n - 1];
+    double t = log(E / emin) / lnr * (double)(n - 1);
+    int k = (int)floor(t);
+    k = k > n - 2 ? n - 2 : (k < 0 ? 0 : k);
+    double f = t - k;
+    return tab[k] + f * (tab[k + 1] - tab[k]);
+}
+
+__device__ inline void iso_dir(double ct, double ph, double s[3]) {
+    double st = sqrt(1.0 - ct * ct);
+    double sp, cp;
+    sincos(ph, &sp, &cp);
+    s[0] = st * cp;
+    s[1] = st * sp;
+    s[2] = ct;
+}
+
+template <typename T>
+__device__ inline int64_t record_event(const MccArgs<T>& a, int kind, uint32_t ida, uint32_t idb) {
+    if (!a.record) return -1;
+    unsigned long long p = atomicAdd(&a.st->n_ev, 1ull);
+    if ((int64_t)p >= a.ev_cap) return -1;
+    pic_event e;
+    e.kind = kind;
+    e.id_a = ida;
+    e.id_b = idb;
+    e.new_ion = kDead;
+    e.new_e = kDead;
+    a.ev[p] = e;
+    return (int64_t)p;
+}
+
+// Decide and apply one pair of class cls (1: e-Cu, 2: Cu+-Cu). ia indexes the
+// charged particle, ib the neutral; pid is the projectile id. Returns the
+// event kind, or 0.
+template <typename T>
+__device__ int resolve_pair(const MccArgs<T>& a, int cls, uint32_t pid, uint32_t ia, uint32_t ib, int NT,
+                            double pnull) {
+    Draw2 d = draw2(a.seed, pid, a.step, cls == 1 ? kTagMcc1 : kTagMcc2, 0);
+    if (d.a >= pnull) return 0;  // null collision
+    const Species<T>& A = a.sp[cls == 1 ? PIC_ELECTRON : PIC_ION];
+    const Species<T>& B = a.sp[PIC_NEUTRAL];
+    double s = a.h / a.dt;
+    double vA[3] = {(double)A.vx[ia], (double)A.vy[ia], (double)A.vz[ia]};
+    double vB[3] = {(double)B.vx[ib], (double)B.vy[ib], (double)B.vz[ib]};
+    double u[3] = {(vA[0] - vB[0]) * s, (vA[1] - vB[1]) * s, (vA[2] - vB[2]) * s};
+    double um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    double mA = cls == 1 ? kMe : a.m_ion;
+    double E = 0.5 * mA * um * um / kQe;
+    double sig0, sig1 = 0.0;
+    if (cls == 1) {
+        sig0 = xs_lookup(a.xs, a.xs_n, a.xs_emin, a.xs_lnr, E);
+        sig1 = (E > a.xi) ? xs_lookup(a.xs + a.xs_n, a.xs_n, a.xs_emin, a.xs_lnr, E) : 0.0;
+    } else {
+        sig0 = xs_lookup(a.xs + 2 * a.xs_n, a.xs_n, a.xs_emin, a.xs_lnr, E);
+    }
+    double stot = sig0 + sig1;
+    double n = (double)NT / (a.h * a.h * a.h);
+    double P = -expm1(-um * n * stot * a.dt);
+    if (!(d.a < P)) return 0;
+    uint32_t idA = A.id[ia], idB = B.id[ib];
+    if (cls == 2) {
+        // charge exchange: the two velocities are exchanged
+        T tx = A.vx[ia], ty = A.vy[ia], tz = A.vz[ia];
+        A.vx[ia] = B.vx[ib];
+        A.vy[ia] = B.vy[ib];
+        A.vz[ia] = B.vz[ib];
+        B.vx[ib] = tx;
+        B.vy[ib] = ty;
+        B.vz[ib] = tz;
+        record_event(a, PIC_EV_CX, idA, idB);
+        return PIC_EV_CX;
+    }
+    bool elastic = d.b * stot < sig0;
+    double g = a.dt / a.h;
+    if (elastic) {
+        // Eq. du: Delta u = R^-1(theta, phi) [R^-1(theta', phi') - I] (0,0,u),
+        // (theta, phi) the direction of u, (theta', phi') isotropic; Eq. newv.
+        Draw2 r = draw2(a.seed, pid, a.step, kTagMcc1, 1);
+        double ct2 = 2.0 * r.a - 1.0, ph2 = 2.0 * kPi * r.b;
+        double up = sqrt(u[0] * u[0] + u[1] * u[1]);
+        double ct = u[2] / um, st = up / um, cp = 1.0, sp = 0.0;
+        if (up > 0.0) {
+            cp = u[0] / up;
+            sp = u[1] / up;
+        }
+        double st2 = sqrt(1.0 - ct2 * ct2);
+        double sp2, cp2;
+        sincos(ph2, &sp2, &cp2);
+        double w0 = um * st2 * cp2, w1 = um * st2 * sp2, w2 = um * (ct2 - 1.0);
+        double du0 = ct * cp * w0 - sp * w1 + st * cp * w2;
+        double du1 = ct * sp * w0 + cp * w1 + st * sp * w2;
+        double du2 = -st * w0 + ct * w2;
+        double mu = mA * a.m_ion / (mA + a.m_ion);
+        double ka = mu / mA * g, kb = mu / a.m_ion * g;
+        A.vx[ia] = (T)(vA[0] + ka * du0);
+        A.vy[ia] = (T)(vA[1] + ka * du1);
+        A.vz[ia] = (T)(vA[2] + ka * du2);
+        B.vx[ib] = (T)(vB[0] - kb * du0);
+        B.vy[ib] = (T)(vB[1] - kb * du1);
+        B.vz[ib] = (T)(vB[2] - kb * du2);
+        record_event(a, PIC_EV_ELASTIC, idA, idB);
+        return PIC_EV_ELASTIC;
+    }
+    // Impact ionization Cu + e -> Cu+ + 2e: in the rest frame of the neutral
+    // the energy above xi is shared as U5 : 1 - U5 by the scattered and the
+    // new electron, both leaving isotropically; the ion keeps the neutral's
+    // position and velocity, the new electron starts at that position.
+    Draw2 r1 = draw2(a.seed, pid, a.step, kTagMcc1, 1);
+    Draw2 r2 = draw2(a.seed, pid, a.step, kTagMcc1, 2);
+    Draw2 r3 = draw2(a.seed, pid, a.step, kTagMcc1, 3);
+    double s1[3], s2[3];
+    iso_dir(2.0 * r1.a - 1.0, 2.0 * kPi * r1.b, s1);
+    iso_dir(2.0 * r2.a - 1.0, 2.0 * kPi * r2.b, s2);
+    double erem = E - a.xi;
+    double e1 = r3.a * erem, e2 = erem - e1;
+    double w1 = sqrt(2.0 * e1 * kQe / kMe), w2 = sqrt(2.0 * e2 * kQe / kMe);
+    double vn[3] = {vB[0] * s, vB[1] * s, vB[2] * s};
+    A.vx[ia] = (T)((vn[0] + w1 * s1[0]) * g);
+    A.vy[ia] = (T)((vn[1] + w1 * s1[1]) * g);
+    A.vz[ia] = (T)((vn[2] + w1 * s1[2]) * g);
+    a.prod_ve[3 * (int64_t)ib + 0] = (vn[0] + w2 * s2[0]) * g;
+    a.prod_ve[3 * (int64_t)ib + 1] = (vn[1] + w2 * s2[1]) * g;
+    a.prod_ve[3 * (int64_t)ib + 2] = (vn[2] + w2 * s2[2]) * g;
+    atomicOr(&a.bitmap_imp[idB >> 5], 1u << (idB & 31));
+    unsigned long long p = atomicAdd(&a.st->n_prod, 1ull);
+    a.prod_list[p] = ib;  // kind 0 (impact)
+    atomicAdd(&a.st->n_prod_kind[0], 1ull);
+    a.prod_ev[ib] = (int32_t)record_event(a, PIC_EV_IONIZE, idA, idB);
+    return PIC_EV_IONIZE;
+}
+
+template <typename T>
+__device__ inline double pnull_of(const MccArgs<T>& a, int cls, int NT) {
+    int sa = cls == 1 ? PIC_ELECTRON : PIC_ION;
+    double umax = ((double)__uint_as_float(a.st->smax_bits[sa]) + (double)__uint_as_float(a.st->smax_bits[2])) *
+                  (1.0 + 0x1p-20);
+    double x = umax * (double)NT * a.xs_max[cls - 1] / (a.h * a.h) * (1.0 + 1e-9);
+    return -expm1(-x);
+}
+
+// Pairs of one class inside one cell, sequentially. Entries are sorted by
+// (species, id); [a0, a0+na) charged species, [b0, b0+nb) neutrals.
+// used: bit r set if the neutral of rank r had an event (input and output).
+template <typename T>
+__device__ void cell_class_seq(const MccArgs<T>& a, int cls, uint32_t cell, const uint64_t* kk, const uint32_t* ee,
+                               int a0, int na, int b0, int nb, uint32_t& used, int cnt[5]) {
+    if (na == 0 || nb == 0) return;
+    bool a_proj = na <= nb;
+    int P0 = a_proj ? a0 : b0, NP = a_proj ? na : nb;
+    int T0 = a_proj ? b0 : a0, NT = a_proj ? nb : na;
+    Draw2 dc = draw2(a.seed, cell, a.step, cls == 1 ? kTagPair1 : kTagPair2, 0);
+    int shift = (int)floor(dc.a * (double)NT);
+    shift = shift > NT - 1 ? NT - 1 : shift;
+    double pnull = pnull_of(a, cls, NT);
+    for (int i = 0; i < NP; ++i) {
+        int pi = P0 + i, ti = T0 + (shift + i) % NT;
+        int ai = a_proj ? pi : ti, bi = a_proj ? ti : pi;
+        int brank = bi - b0;
+        if (cls == 2 && ((used >> brank) & 1u)) continue;
+        uint32_t pid = (uint32_t)(kk[pi] & 0xFFFFFFFFu);
+        int kind = resolve_pair(a, cls, pid, ee[ai] & 0x3FFFFFFFu, ee[bi] & 0x3FFFFFFFu, NT, pnull);
+        if (kind) {
+            used |= 1u << brank;
+            a.nflag[ee[bi] & 0x3FFFFFFFu] = a.step + 1u;
+            cnt[kind]++;
+        }
+    }
+}
+
+template <typename T>
+__device__ inline void flush_counts(DevState* st, int cnt[5]) {
+    __shared__ int sh[kBlock / 64];
+    for (int k = 1; k <= 3; ++k) {
+        int t = block_sum(cnt[k], sh);
+        if (threadIdx.x == 0 && t) atomicAdd(&st->events[k], (unsigned long long)t);
+    }
+}
+
+// One thread per cell with at most kSmallCell particles; larger cells are
+// queued for the wavefront kernel.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mcc_small(MccArgs<T> a) {
+    int cnt[5] = {0, 0, 0, 0, 0};
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.nc; c += stride) {
+        uint32_t o0 = a.off[c];
+        int n = (int)(a.off[c + 1] - o0);
+        if (n < 2) continue;
+        if (n > kSmallCell) {
+            unsigned long long p = atomicAdd(&a.st->n_big, 1ull);
+            a.big[p] = (uint32_t)c;
+            continue;
+        }
+        uint64_t kk[kSmallCell];
+        uint32_t ee[kSmallCell];
+        for (int t = 0; t < n; ++t) {
+            uint32_t e = a.bins[o0 + t];
+            uint32_t s = e >> 30;
+            uint32_t id = a.sp[s].id[e & 0x3FFFFFFFu];
+            uint64_t k = ((uint64_t)s << 32) | id;
+            int u = t;
+            while (u > 0 && kk[u - 1] > k) {
+                kk[u] = kk[u - 1];
+                ee[u] = ee[u - 1];
+                --u;
+            }
+            kk[u] = k;
+            ee[u] = e;
+        }
+        if (a.write_sorted)
+            for (int t = 0; t < n; ++t) a.bins[o0 + t] = ee[t];
+        int ne = 0, ni = 0;
+        for (int t = 0; t < n; ++t) {
+            uint32_t s = (uint32_t)(kk[t] >> 32);
+            ne += s == 0;
+            ni += s == 1;
+        }
+        int nn = n - ne - ni;
+        uint32_t used = 0;
+        cell_class_seq(a, 1, (uint32_t)c, kk, ee, 0, ne, ne + ni, nn, used, cnt);
+        cell_class_seq(a, 2, (uint32_t)c, kk, ee, ne, ni, ne + ni, nn, used, cnt);
+    }
+    flush_counts<T>(a.st, cnt);
+}
+
+// One wavefront per cell with more than kSmallCell particles: bitonic sort of
+// the (species, id) keys in LDS, then projectiles handled across the lanes.
+template <typename T>
+__global__ __launch_bounds__(64) void k_mcc_big(MccArgs<T> a) {
+    __shared__ uint64_t kk[kBigCell];
+    __shared__ uint32_t ee[kBigCell];
+    __shared__ uint8_t used[kBigCell];
+    int cnt[5] = {0, 0, 0, 0, 0};
+    const int lane = threadIdx.x;
+    const int64_t nbig = (int64_t)a.st->n_big;
+    for (int64_t b = blockIdx.x; b < nbig; b += gridDim.x) {
+        uint32_t c = a.big[b];
+        uint32_t o0 = a.off[c];
+        int n = (int)(a.off[c + 1] - o0);
+        if (n > kBigCell) {
+            if (lane == 0) atomicCAS(&a.st->error, 0, PIC_E_CAPACITY);
+            continue;
+        }
+        int P = 1;
+        while (P < n) P <<= 1;
+        for (int t = lane; t < P; t += 64) {
+            if (t < n) {
+                uint32_t e = a.bins[o0 + t];
+                uint32_t s = e >> 30;
+                kk[t] = ((uint64_t)s << 32) | a.sp[s].id[e & 0x3FFFFFFFu];
+                ee[t] = e;
+            } else {
+                kk[t] = ~0ull;
+                ee[t] = 0;
+            }
+            used[t] = 0;
+        }
+        __syncthreads();
+        for (int k = 2; k <= P; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int t = lane; t < P; t += 64) {
+                    int u = t ^ j;
+                    if (u > t) {
+                        bool up = (t & k) == 0;
+                        uint64_t x = kk[t], y = kk[u];
+                        if ((x > y) == up) {
+                            kk[t] = y;
+                            kk[u] = x;
+                            uint32_t ex = ee[t];
+                            ee[t] = ee[u];
+                            ee[u] = ex;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        if (a.write_sorted)
+            for (int t = lane; t < n; t += 64) a.bins[o0 + t] = ee[t];
+        int ne = 0, ni = 0;
+        for (int t = lane; t < n; t += 64) {
+            uint32_t s = (uint32_t)(kk[t] >> 32);
+            ne += s == 0;
+            ni += s == 1;
+        }
+        ne = wave_sum(ne);
+        ni = wave_sum(ni);
+        int nn = n - ne - ni;
+        for (int cls = 1; cls <= 2; ++cls) {
+            int a0 = cls == 1 ? 0 : ne, na = cls == 1 ? ne : ni, b0 = ne + ni, nb = nn;
+            if (na > 0 && nb > 0) {
+                bool a_proj = na <= nb;
+                int P0 = a_proj ? a0 : b0, NP = a_proj ? na : nb;
+                int T0 = a_proj ? b0 : a0, NT = a_proj ? nb : na;
+                Draw2 dc = draw2(a.seed, c, a.step, cls == 1 ? kTagPair1 : kTagPair2, 0);
+                int shift = (int)floor(dc.a * (double)NT);
+                shift = shift > NT - 1 ? NT - 1 : shift;
+                double pnull = pnull_of(a, cls, NT);
+                for (int i = lane; i < NP; i += 64) {
+                    int pi = P0 + i, ti = T0 + (shift + i) % NT;
+                    int ai = a_proj ? pi : ti, bi = a_proj ? ti : pi;
+                    if (cls == 2 && used[bi]) continue;
+                    uint32_t pid = (uint32_t)(kk[pi] & 0xFFFFFFFFu);
+                    int kind = resolve_pair(a, cls, pid, ee[ai] & 0x3FFFFFFFu, ee[bi] & 0x3FFFFFFFu, NT, pnull);
+                    if (kind) {
+                        used[bi] = 1;
+                        a.nflag[ee[bi] & 0x3FFFFFFFu] = a.step + 1u;
+                        cnt[kind]++;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int k = 1; k <= 3; ++k) {
+        int t = wave_sum(cnt[k]);
+        if (lane == 0 && t) atomicAdd(&a.st->events[k], (unsigned long long)t);
+    }
+}
+
+// Field ionization of the candidates whose neutral had no collision event.
+template <typename T>
+__global__ void k_fi_resolve(MccArgs<T> a, const uint32_t* fi_list, uint32_t* bitmap_fi) {
+    int64_t n = (int64_t)a.st->n_fi;
+    int cnt = 0;
+    const Species<T>& N = a.sp[PIC_NEUTRAL];
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        uint32_t ib = fi_list[i];
+        if (a.nflag[ib] == a.step + 1u) continue;
+        a.nflag[ib] = a.step + 1u;
+        uint32_t id = N.id[ib];
+        atomicOr(&bitmap_fi[id >> 5], 1u << (id & 31));
+        a.prod_ve[3 * (int64_t)ib + 0] = (double)N.vx[ib];
+        a.prod_ve[3 * (int64_t)ib + 1] = (double)N.vy[ib];
+        a.prod_ve[3 * (int64_t)ib + 2] = (double)N.vz[ib];
+        unsigned long long p = atomicAdd(&a.st->n_prod, 1ull);
+        a.prod_list[p] = ib | 0x80000000u;
+        atomicAdd(&a.st->n_prod_kind[1], 1ull);
+        a.prod_ev[ib] = (int32_t)record_event(a, PIC_EV_FIELD_ION, kDead, id);
+        ++cnt;
+    }
+    __shared__ int sh[kBlock / 64];
+    int t = block_sum(cnt, sh);
+    if (threadIdx.x == 0 && t) atomicAdd(&a.st->events[PIC_EV_FIELD_ION], (unsigned long long)t);
+}
+
+// ---------------------------------------------------------------------------
+// Products of ionization. They are numbered in the order (impact before
+// field ionization, ascending neutral id): the rank of a product is the
+// number of products before it in that order, read from per-kind bitmaps over
+// the id space and their word prefix counts. Each product takes the ids
+// next_id + 2 rank (ion) and next_id + 2 rank + 1 (electron) and the slots
+// n_slots + rank of the ion and electron arrays; the neutral's slot is freed.
+
+template <typename T>
+struct ProdArgs {
+    Species<T> sp[3];
+    DevState* st;
+    const uint32_t* prod_list;
+    const double* prod_ve;
+    const int32_t* prod_ev;
+    uint32_t* bitmap[2];
+    const uint32_t* prefix[2];
+    pic_event* ev;
+    int64_t ev_cap;
+};
+
+template <typename T>
+__global__ void k_products(ProdArgs<T> a) {
+    int64_t n = (int64_t)a.st->n_prod;
+    if (n == 0) return;
+    Species<T>& I = a.sp[PIC_ION];
+    Species<T>& El = a.sp[PIC_ELECTRON];
+    Species<T>& N = a.sp[PIC_NEUTRAL];
+    int64_t base_i = (int64_t)a.st->n_slots[PIC_ION], base_e = (int64_t)a.st->n_slots[PIC_ELECTRON];
+    bool room = base_i + n <= I.cap && base_e + n <= El.cap;
+    uint32_t nid0 = (uint32_t)a.st->next_id;
+    int64_t nimp = (int64_t)a.st->n_prod_kind[0];
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+        uint32_t e = a.prod_list[p];
+        int kind = e >> 31;
+        uint32_t ib = e & 0x7FFFFFFFu;
+        uint32_t id = N.id[ib];
+        uint32_t w = a.bitmap[kind][id >> 5];
+        int64_t r = (int64_t)a.prefix[kind][id >> 5] + __popc(w & ((1u << (id & 31)) - 1u));
+        if (kind == 1) r += nimp;
+        if (!room) continue;
+        int64_t si = base_i + r, se = base_e + r;
+        uint32_t id_ion = nid0 + 2u * (uint32_t)r, id_e = id_ion + 1u;
+        T x = N.x[ib], y = N.y[ib], z = N.z[ib];
+        I.x[si] = x;
+        I.y[si] = y;
+        I.z[si] = z;
+        I.vx[si] = N.vx[ib];
+        I.vy[si] = N.vy[ib];
+        I.vz[si] = N.vz[ib];
+        I.id[si] = id_ion;
+        El.x[se] = x;
+        El.y[se] = y;
+        El.z[se] = z;
+        El.vx[se] = (T)a.prod_ve[3 * (int64_t)ib + 0];
+        El.vy[se] = (T)a.prod_ve[3 * (int64_t)ib + 1];
+        El.vz[se] = (T)a.prod_ve[3 * (int64_t)ib + 2];
+        El.id[se] = id_e;
+        int32_t q = a.prod_ev[ib];
+        if (q >= 0 && q < a.ev_cap) {
+            a.ev[q].new_ion = id_ion;
+            a.ev[q].new_e = id_e;
+        }
+    }
+}
+
+// Second pass: clear the bitmap bits and free the neutral slots.
+template <typename T>
+__global__ void k_products_clear(ProdArgs<T> a) {
+    int64_t n = (int64_t)a.st->n_prod;
+    Species<T>& N = a.sp[PIC_NEUTRAL];
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+        uint32_t e = a.prod_list[p];
+        int kind = e >> 31;
+        uint32_t ib = e & 0x7FFFFFFFu;
+        uint32_t id = N.id[ib];
+        atomicAnd(&a.bitmap[kind][id >> 5], ~(1u << (id & 31)));
+        N.id[ib] = kDead;
+    }
+}
+
+__global__ void k_products_finish(DevState* st, int64_t cap_e, int64_t cap_i) {
+    unsigned long long n = st->n_prod;
+    if (st->n_slots[PIC_ION] + n > (unsigned long long)cap_i || st->n_slots[PIC_ELECTRON] + n > (unsigned long long)cap_e) {
+        if (n) atomicCAS(&st->error, 0, PIC_E_CAPACITY);
+        return;
+    }
+    st->n_slots[PIC_ION] += n;
+    st->n_slots[PIC_ELECTRON] += n;
+    st->next_id += 2ull * n;
+}
+
+// Number of bitmap words in use, (next_id + 31) / 32, for the device-sized scan.
+__global__ void k_words(const DevState* st, uint32_t* words, int64_t maxw) {
+    unsigned long long w = (st->next_id + 31ull) >> 5;
+    if (st->n_prod == 0) w = 0;
+    *words = (uint32_t)(w < (unsigned long long)maxw ? w : (unsigned long long)maxw);
+}
+
+// ---------------------------------------------------------------------------
+// Reordering by cell: the alive particles of a species take the order of the
+// (canonically sorted) cell bins; particles appended after the bins were
+// built (products) follow in their order.
+
+__global__ void k_sort_flags(int sp, const uint32_t* bins, const uint32_t* nbins, const uint32_t* const* ids,
+                             uint32_t* flag, int64_t cap) {
+    int64_t n = (int64_t)*nbins;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n && j < cap; j += stride) {
+        uint32_t e = bins[j];
+        uint32_t s = e >> 30;
+        flag[j] = (s == (uint32_t)sp) && ids[s][e & 0x3FFFFFFFu] != kDead;
+    }
+}
+
+template <typename T>
+struct SortArgs {
+    Species<T> s;
+    int sp;
+    const uint32_t* bins;
+    const uint32_t* nbins;
+    const uint32_t* flag;   // flags (before the scan)
+    const uint32_t* rank;   // exclusive ranks
+    const uint32_t* total;  // number of sorted particles
+    T* tmp;                 // 6 * cap
+    uint32_t* tmp_id;
+    DevState* st;
+};
+
+template <typename T>
+__global__ void k_sort_gather(SortArgs<T> a) {
+    int64_t n = (int64_t)*a.nbins;
+    int64_t cap = a.s.cap;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
+        uint32_t e = a.bins[j];
+        if ((e >> 30) != (uint32_t)a.sp) continue;
+        uint32_t i = e & 0x3FFFFFFFu;
+        if (a.s.id[i] == kDead) continue;
+        int64_t d = a.rank[j];
+        a.tmp[d] = a.s.x[i];
+        a.tmp[cap + d] = a.s.y[i];
+        a.tmp[2 * cap + d] = a.s.z[i];
+        a.tmp[3 * cap + d] = a.s.vx[i];
+        a.tmp[4 * cap + d] = a.s.vy[i];
+        a.tmp[5 * cap + d] = a.s.vz[i];
+        a.tmp_id[d] = a.s.id[i];
+    }
+    // particles appended after the bins were built
+    int64_t p0 = (int64_t)a.st->n_push[a.sp], p1 = (int64_t)a.st->n_slots[a.sp];
+    int64_t ns = (int64_t)*a.total;
+    for (int64_t i = p0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < p1; i += stride) {
+        int64_t d = ns + (i - p0);
+        a.tmp[d] = a.s.x[i];
+        a.tmp[cap + d] = a.s.y[i];
+        a.tmp[2 * cap + d] = a.s.z[i];
+        a.tmp[3 * cap + d] = a.s.vx[i];
+        a.tmp[4 * cap + d] = a.s.vy[i];
+        a.tmp[5 * cap + d] = a.s.vz[i];
+        a.tmp_id[d] = a.s.id[i];
+    }
+}
+
+template <typename T>
+__global__ void k_sort_copyback(SortArgs<T> a) {
+    int64_t ns = (int64_t)*a.total + ((int64_t)a.st->n_slots[a.sp] - (int64_t)a.st->n_push[a.sp]);
+    int64_t cap = a.s.cap;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += stride) {
+        a.s.x[i] = a.tmp[i];
+        a.s.y[i] = a.tmp[cap + i];
+        a.s.z[i] = a.tmp[2 * cap + i];
+        a.s.vx[i] = a.tmp[3 * cap + i];
+        a.s.vy[i] = a.tmp[4 * cap + i];
+        a.s.vz[i] = a.tmp[5 * cap + i];
+        a.s.id[i] = a.tmp_id[i];
+    }
+}
+
+__global__ void k_sort_finish(DevState* st, int sp, const uint32_t* total) {
+    unsigned long long ns = (unsigned long long)*total + (st->n_slots[sp] - st->n_push[sp]);
+    st->n_slots[sp] = ns;
+    st->n_push[sp] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// Per-step reset of the counters of one push/deposit pass.
+__global__ void k_step_reset(DevState* st) {
+    st->n_fi = 0;
+    st->n_prod = 0;
+    st->n_prod_kind[0] = st->n_prod_kind[1] = 0;
+    st->n_ev = 0;
+    st->n_big = 0;
+    for (int s = 0; s < 3; ++s) {
+        st->smax_bits[s] = 0;
+        st->n_push[s] = st->n_slots[s];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host drivers
+
+template <typename T>
+static Species<T> species(pic_ctx* c, int s) {
+    Species<T> r;
+    r.x = (T*)c->buf.x[s];
+    r.y = (T*)c->buf.y[s];
+    r.z = (T*)c->buf.z[s];
+    r.vx = (T*)c->buf.vx[s];
+    r.vy = (T*)c->buf.vy[s];
+    r.vz = (T*)c->buf.vz[s];
+    r.id = c->buf.id[s];
+    r.cap = c->buf.cap[s];
+    return r;
+}
+
+static unsigned grid_for(int64_t n) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
+template <typename T>
+static hipError_t particles_t(pic_ctx* c, bool move) {
+    const pic_config& cf = c->cfg;
+    hipLaunchKernelGGL(k_step_reset, dim3(1), dim3(1), 0, c->stream, c->st);
+    (void)launch_zero(c->buf.rho, sizeof(int64_t) * c->g.nn, c->stream);
+    if (c->bins_dirty) (void)launch_zero(c->cnt, sizeof(uint32_t) * c->g.nc, c->stream);
+    for (int s = 0; s < 3; ++s) {
+        PushArgs<T> a;
+        a.s = species<T>(c, s);
+        a.field = (const typename V4<T>::type*)c->buf.field;
+        a.g = c->g;
+        a.kq = (T)c->kq[s];
+        a.rho = c->buf.rho;
+        a.sign = s == PIC_ELECTRON ? -1 : 1;
+        a.cnt = c->cnt;
+        a.key = c->key[s];
+        a.slot = c->slot[s];
+        a.st = c->st;
+        a.step = (uint32_t)c->step;
+        a.seed = cf.seed;
+        a.fi_list = c->fi_list;
+        a.fi_thr = c->fi_thr;
+        a.ebsi = c->ebsi;
+        a.adk_c = c->adk_c;
+        a.adk_e = 2.0 * c->adk_n - 1.0;
+        a.x32 = pow(cf.xi, 1.5);
+        a.dt_fs = cf.dt * 1e15;
+        unsigned G = grid_for(a.s.cap);
+        if (move) {
+            if (s == 0) hipLaunchKernelGGL((k_push<T, 0, true>), dim3(G), dim3(kBlock), 0, c->stream, a);
+            if (s == 1) hipLaunchKernelGGL((k_push<T, 1, true>), dim3(G), dim3(kBlock), 0, c->stream, a);
+            if (s == 2) hipLaunchKernelGGL((k_push<T, 2, true>), dim3(G), dim3(kBlock), 0, c->stream, a);
+        } else {
+            if (s == 0) hipLaunchKernelGGL((k_push<T, 0, false>), dim3(G), dim3(kBlock), 0, c->stream, a);
+            if (s == 1) hipLaunchKernelGGL((k_push<T, 1, false>), dim3(G), dim3(kBlock), 0, c->stream, a);
+            if (s == 2) hipLaunchKernelGGL((k_push<T, 2, false>), dim3(G), dim3(kBlock), 0, c->stream, a);
+        }
+    }
+    c->bins_dirty = 1;
+    c->bins_valid = 1;
+    return hipGetLastError();
+}
+
+hipError_t particles_phase(pic_ctx* c, bool move) {
+    return c->cfg.precision == PIC_F32 ? particles_t<float>(c, move) : particles_t<double>(c, move);
+}
+
+template <typename T>
+static hipError_t collide_t(pic_ctx* c, bool record) {
+    const pic_config& cf = c->cfg;
+    const Grid& g = c->g;
+    // cell offsets (and counters cleared for the next pass), then the bins
+    hipError_t e = scan_u32(c, c->cnt, c->off, g.nc, nullptr, c->off + g.nc, true, false);
+    if (e != hipSuccess) return e;
+    c->bins_dirty = 0;
+    for (int s = 0; s < 3; ++s)
+        hipLaunchKernelGGL(k_scatter, dim3(grid_for(c->buf.cap[s])), dim3(kBlock), 0, c->stream, s, c->key[s],
+                           c->slot[s], c->off, c->bins, c->st);
+    bool resort = cf.sort_every > 0 && ((c->collide_count + 1) % cf.sort_every) == 0;
+    MccArgs<T> a;
+    for (int s = 0; s < 3; ++s) a.sp[s] = species<T>(c, s);
+    a.off = c->off;
+    a.bins = c->bins;
+    a.nc = g.nc;
+    a.big = c->big;
+    a.st = c->st;
+    a.step = (uint32_t)c->step;
+    a.seed = cf.seed;
+    a.h = cf.h;
+    a.dt = cf.dt;
+    a.m_ion = cf.m_ion;
+    a.xi = cf.xi;
+    a.xs = c->xs;
+    a.xs_n = cf.xs_n;
+    a.xs_emin = cf.xs_emin;
+    a.xs_lnr = log(cf.xs_emax / cf.xs_emin);
+    a.xs_max[0] = c->xs_max[0];
+    a.xs_max[1] = c->xs_max[1];
+    a.nflag = c->nflag;
+    a.bitmap_imp = c->bitmap[0];
+    a.prod_list = c->prod_list;
+    a.prod_ve = c->prod_ve;
+    a.prod_ev = c->prod_ev;
+    a.ev = c->ev;
+    a.ev_cap = c->ev_cap;
+    a.record = record ? 1 : 0;
+    a.write_sorted = resort ? 1 : 0;
+    hipLaunchKernelGGL(k_mcc_small<T>, dim3(grid_for(g.nc)), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(k_mcc_big<T>, dim3(1024), dim3(64), 0, c->stream, a);
+    hipLaunchKernelGGL(k_fi_resolve<T>, dim3(grid_for(c->buf.cap[2])), dim3(kBlock), 0, c->stream, a, c->fi_list,
+                       c->bitmap[1]);
+    // products
+    uint32_t* words = c->dyn;
+    hipLaunchKernelGGL(k_words, dim3(1), dim3(1), 0, c->stream, c->st, words, c->bm_words);
+    for (int k = 0; k < 2; ++k) {
+        e = scan_u32(c, c->bitmap[k], c->bm_prefix[k], c->bm_words, words, nullptr, false, true);
+        if (e != hipSuccess) return e;
+    }
+    ProdArgs<T> p;
+    for (int s = 0; s < 3; ++s) p.sp[s] = species<T>(c, s);
+    p.st = c->st;
+    p.prod_list = c->prod_list;
+    p.prod_ve = c->prod_ve;
+    p.prod_ev = c->prod_ev;
+    p.bitmap[0] = c->bitmap[0];
+    p.bitmap[1] = c->bitmap[1];
+    p.prefix[0] = c->bm_prefix[0];
+    p.prefix[1] = c->bm_prefix[1];
+    p.ev = c->ev;
+    p.ev_cap = c->ev_cap;
+    unsigned Gp = grid_for(c->buf.cap[2]);
+    hipLaunchKernelGGL(k_products<T>, dim3(Gp), dim3(kBlock), 0, c->stream, p);
+    hipLaunchKernelGGL(k_products_clear<T>, dim3(Gp), dim3(kBlock), 0, c->stream, p);
+    hipLaunchKernelGGL(k_products_finish, dim3(1), dim3(1), 0, c->stream, c->st, c->buf.cap[0], c->buf.cap[1]);
+    if (resort) {
+        uint32_t* flag = c->rank_flag;
+        int64_t capsum = c->buf.cap[0] + c->buf.cap[1] + c->buf.cap[2];
+        for (int s = 0; s < 3; ++s) {
+            hipLaunchKernelGGL(k_sort_flags, dim3(grid_for(capsum)), dim3(kBlock), 0, c->stream, s, c->bins,
+                               c->off + g.nc, (const uint32_t* const*)c->id_ptrs, flag, capsum);
+            e = scan_u32(c, flag, c->rank, capsum, c->off + g.nc, c->dyn + 1, false, false);
+            if (e != hipSuccess) return e;
+            SortArgs<T> sa;
+            sa.s = species<T>(c, s);
+            sa.sp = s;
+            sa.bins = c->bins;
+            sa.nbins = c->off + g.nc;
+            sa.flag = flag;
+            sa.rank = c->rank;
+            sa.total = c->dyn + 1;
+            sa.tmp = (T*)c->tmp;
+            sa.tmp_id = (uint32_t*)((T*)c->tmp + 6 * c->tmp_cap);
+            sa.st = c->st;
+            hipLaunchKernelGGL(k_sort_gather<T>, dim3(grid_for(capsum)), dim3(kBlock), 0, c->stream, sa);
+            hipLaunchKernelGGL(k_sort_copyback<T>, dim3(grid_for(sa.s.cap)), dim3(kBlock), 0, c->stream, sa);
+            hipLaunchKernelGGL(k_sort_finish, dim3(1), dim3(1), 0, c->stream, c->st, s, c->dyn + 1);
+        }
+    }
+    c->collide_count++;
+    c->bins_valid = 0;
+    return hipGetLastError();
+}
+
+hipError_t collide_phase(pic_ctx* c, bool record) {
+    return c->cfg.precision == PIC_F32 ? collide_t<float>(c, record) : collide_t<double>(c, record);
+}
+
+// ---------------------------------------------------------------------------
+// Field emission (Sec. 2.3.1): per patch of the analytic tip surface, the
+// field one spacing out along the normal gives the Murphy-Good current
+// density J; N = J A dt / e electrons are expected, floor(N) are injected
+// plus one with probability frac(N), uniformly on the patch, 10^-3 spacings
+// outside the surface, at rest. Ids follow patch order. One block does it all.
+
+struct InjArgs {
+    Grid g;
+    const double* phi;
+    int rings, naz;
+    int64_t npatch;
+    double fn_a, fn_b, fn_cs2, phi_w, h, dt;
+    uint64_t seed;
+    uint32_t step;
+    DevState* st;
+    int64_t cap;
+};
+
+__device__ inline double interp_phi(const Grid& g, const double* phi, double X, double Y, double Z) {
+    int i = clampi((int)floor(X), 0, g.nx - 2), j = clampi((int)floor(Y), 0, g.ny - 2),
+        k = clampi((int)floor(Z), 0, g.nz - 2);
+    double fx = X - i, fy = Y - j, fz = Z - k;
+    double s = 0.0;
+    for (int t = 0; t < 8; ++t) {
+        double w = ((t & 1) ? fx : 1.0 - fx) * ((t & 2) ? fy : 1.0 - fy) * ((t & 4) ? fz : 1.0 - fz);
+        int64_t m = ((int64_t)(k + ((t >> 2) & 1)) * g.ny + j + ((t >> 1) & 1)) * g.nx + i + (t & 1);
+        s += w * phi[m];
+    }
+    return s;
+}
+
+// point on patch p for uniforms (ua, ub): out = {X, Y, Z, nx, ny, nz, area}
+__device__ inline void patch_point(const InjArgs& a, int64_t p, double ua, double ub, double out[7]) {
+    const Grid& g = a.g;
+    int64_t ring = p / a.naz, az = p % a.naz;
+    double ph = 2.0 * kPi * ((double)az + ub) / (double)a.naz;
+    double sp, cp;
+    sincos(ph, &sp, &cp);
+    if (ring < a.rings) {
+        double ct = 1.0 - ((double)ring + ua) / (double)a.rings;
+        double st = sqrt(1.0 - ct * ct);
+        double nx = st * cp, ny = st * sp, nz = ct;
+        out[0] = g.xc + g.R * nx;
+        out[1] = g.yc + g.R * ny;
+        out[2] = g.zc + g.R * nz;
+        out[3] = nx;
+        out[4] = ny;
+        out[5] = nz;
+        out[6] = 2.0 * kPi * g.R * g.R / (double)a.rings / (double)a.naz;
+    } else {
+        int64_t q = ring - a.rings;
+        double zlo = (double)q, zhi = fmin((double)(q + 1), g.zc);
+        out[0] = g.xc + g.R * cp;
+        out[1] = g.yc + g.R * sp;
+        out[2] = zlo + ua * (zhi - zlo);
+        out[3] = cp;
+        out[4] = sp;
+        out[5] = 0.0;
+        out[6] = 2.0 * kPi * g.R * (zhi - zlo) / (double)a.naz;
+    }
+}
+
+__device__ inline int64_t patch_count(const InjArgs& a, int64_t p, double* nexp, int* clamped) {
+    double q[7];
+    patch_point(a, p, 0.5, 0.5, q);
+    double F = interp_phi(a.g, a.phi, q[0] + q[3], q[1] + q[4], q[2] + q[5]) / a.h;
+    double J = 0.0;
+    *clamped = 0;
+    if (F > 0.0) {
+        double f = a.fn_cs2 * F / (a.phi_w * a.phi_w);
+        if (f > 1.0) {
+            f = 1.0;
+            *clamped = 1;
+        }
+        double lf = log(f);
+        double v = 1.0 - f + (f / 6.0) * lf;
+        double t = 1.0 + f / 9.0 - (f / 18.0) * lf;
+        J = a.fn_a * F * F / (a.phi_w * t * t) * exp(-v * a.fn_b * pow(a.phi_w, 1.5) / F);
+    }
+    double N = J * q[6] * a.h * a.h * a.dt / kQe;
+    *nexp = N;
+    Draw2 u = draw2(a.seed, (uint32_t)p, a.step, kTagInj, 0);
+    double fl = floor(N);
+    return (int64_t)fl + ((u.a < N - fl) ? 1 : 0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_inject(InjArgs a, Species<T> e) {
+    __shared__ int64_t sh[1024];
+    __shared__ double shd[16];
+    __shared__ int64_t total_sh;
+    const int B = blockDim.x;
+    // pass 1: totals
+    int64_t tot = 0, ncl = 0;
+    double nexp_acc = 0.0;
+    for (int64_t r0 = 0; r0 < a.npatch; r0 += B) {
+        int64_t p = r0 + threadIdx.x;
+        double ne = 0.0;
+        int cl = 0;
+        int64_t k = p < a.npatch ? patch_count(a, p, &ne, &cl) : 0;
+        tot += k;
+        ncl += cl;
+        double s = block_sum(ne, shd);
+        if (threadIdx.x == 0) nexp_acc += s;
+    }
+    __shared__ int64_t shi[16];
+    int64_t T1 = block_sum(tot, shi);
+    int64_t C1 = block_sum(ncl, shi);
+    if (threadIdx.x == 0) {
+        total_sh = T1;
+        a.st->fn_expected += nexp_acc;
+        a.st->fn_clamped += (unsigned long long)C1;
+    }
+    __syncthreads();
+    int64_t total = total_sh;
+    int64_t base = (int64_t)a.st->n_slots[PIC_ELECTRON];
+    uint32_t id0 = (uint32_t)a.st->next_id;
+    if (total == 0) return;
+    if (base + total > a.cap) {
+        if (threadIdx.x == 0) atomicCAS(&a.st->error, 0, PIC_E_CAPACITY);
+        return;
+    }
+    // pass 2: offsets in patch order and the electrons
+    int64_t carry = 0;
+    for (int64_t r0 = 0; r0 < a.npatch; r0 += B) {
+        int64_t p = r0 + threadIdx.x;
+        double ne;
+        int cl;
+        int64_t k = p < a.npatch ? patch_count(a, p, &ne, &cl) : 0;
+        sh[threadIdx.x] = k;
+        __syncthreads();
+        for (int o = 1; o < B; o <<= 1) {
+            int64_t add = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += add;
+            __syncthreads();
+        }
+        int64_t off = carry + sh[threadIdx.x] - k;
+        for (int64_t j = 0; j < k; ++j) {
+            Draw2 u = draw2(a.seed, (uint32_t)p, a.step, kTagInj, (uint32_t)(1 + j));
+            double q[7];
+            patch_point(a, p, u.a, u.b, q);
+            int64_t m = base + off + j;
+            e.x[m] = (T)(q[0] + 1e-3 * q[3]);
+            e.y[m] = (T)(q[1] + 1e-3 * q[4]);
+            e.z[m] = (T)(q[2] + 1e-3 * q[5]);
+            e.vx[m] = (T)0;
+            e.vy[m] = (T)0;
+            e.vz[m] = (T)0;
+            e.id[m] = id0 + (uint32_t)(off + j);
+        }
+        int64_t last = sh[B - 1];
+        __syncthreads();
+        carry += last;
+    }
+    if (threadIdx.x == 0) {
+        a.st->n_slots[PIC_ELECTRON] += (unsigned long long)total;
+        a.st->next_id += (unsigned long long)total;
+        a.st->injected += (unsigned long long)total;
+    }
+}
+
+hipError_t inject_phase(pic_ctx* c) {
+    InjArgs a;
+    a.g = c->g;
+    a.phi = c->buf.phi;
+    a.rings = c->cfg.fn_rings;
+    a.naz = c->cfg.fn_az;
+    a.npatch = c->npatch;
+    a.fn_a = kQe * kQe / (8.0 * kPi * kHpl);
+    a.fn_b = (8.0 * kPi / 3.0) * sqrt(2.0 * kMe) / (kQe * kHpl) * pow(kQe, 1.5);
+    a.fn_cs2 = kQe / (4.0 * kPi * kEps0);
+    a.phi_w = c->cfg.phi_w;
+    a.h = c->cfg.h;
+    a.dt = c->cfg.dt;
+    a.seed = c->cfg.seed;
+    a.step = (uint32_t)c->step;
+    a.st = c->st;
+    a.cap = c->buf.cap[0];
+    if (c->npatch == 0) return hipSuccess;
+    if (c->cfg.precision == PIC_F32)
+        hipLaunchKernelGGL(k_inject<float>, dim3(1), dim3(1024), 0, c->stream, a, species<float>(c, 0));
+    else
+        hipLaunchKernelGGL(k_inject<double>, dim3(1), dim3(1024), 0, c->stream, a, species<double>(c, 0));
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Explicit load: append n particles, numbered from next_id in array order.
+
+template <typename T>
+__global__ void k_load(Species<T> s, int sp, const T* x, const T* y, const T* z, const T* vx, const T* vy,
+                       const T* vz, int64_t n, DevState* st) {
+    int64_t base = (int64_t)st->n_slots[sp];
+    if (base + n > s.cap) return;
+    uint32_t id0 = (uint32_t)st->next_id;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        int64_t m = base + i;
+        s.x[m] = x[i];
+        s.y[m] = y[i];
+        s.z[m] = z[i];
+        s.vx[m] = vx[i];
+        s.vy[m] = vy[i];
+        s.vz[m] = vz[i];
+        s.id[m] = id0 + (uint32_t)i;
+    }
+}
+
+__global__ void k_load_finish(DevState* st, int sp, int64_t n, int64_t cap) {
+    if ((int64_t)st->n_slots[sp] + n > cap) {
+        atomicCAS(&st->error, 0, PIC_E_CAPACITY);
+        return;
+    }
+    st->n_slots[sp] += (unsigned long long)n;
+    st->next_id += (unsigned long long)n;
+}
+
+hipError_t load_particles(pic_ctx* c, const pic_particles* src) {
+    int s = src->species;
+    if (src->n == 0) return hipSuccess;
+    if (c->cfg.precision == PIC_F32) {
+        hipLaunchKernelGGL(k_load<float>, dim3(grid_for(src->n)), dim3(kBlock), 0, c->stream, species<float>(c, s), s,
+                           (const float*)src->x, (const float*)src->y, (const float*)src->z, (const float*)src->vx,
+                           (const float*)src->vy, (const float*)src->vz, src->n, c->st);
+    } else {
+        hipLaunchKernelGGL(k_load<double>, dim3(grid_for(src->n)), dim3(kBlock), 0, c->stream, species<double>(c, s),
+                           s, (const double*)src->x, (const double*)src->y, (const double*)src->z,
+                           (const double*)src->vx, (const double*)src->vy, (const double*)src->vz, src->n, c->st);
+    }
+    hipLaunchKernelGGL(k_load_finish, dim3(1), dim3(1), 0, c->stream, c->st, s, src->n, c->buf.cap[s]);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Moments: per species the alive count and kinetic energy, and the
+// Shockley-Ramo current I = sum q v . E0(x) (Sec. 2.3.1) with E0 the field of
+// the unit-anode Laplace problem. Fixed grid and fixed-order reductions.
+// out (device, per block): 7 doubles {n_e, n_i, n_n, ke_e, ke_i, ke_n, i_sr}.
+
+constexpr int kMomBlocks = 512;
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_moments(Species<T> s0, Species<T> s1, Species<T> s2,
+                                                     const typename V4<T>::type* E0, Grid g, double sv, double m_ion,
+                                                     const DevState* st, double* part) {
+    __shared__ double sh[kBlock / 64];
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    const Species<T>* S[3] = {&s0, &s1, &s2};
+    const double mass[3] = {kMe, m_ion, m_ion};
+    const double q[3] = {-kQe, kQe, 0.0};
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int s = 0; s < 3; ++s) {
+        int64_t n = (int64_t)st->n_slots[s];
+        const Species<T>& P = *S[s];
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+            if (P.id[i] == kDead) continue;
+            double vx = (double)P.vx[i] * sv, vy = (double)P.vy[i] * sv, vz = (double)P.vz[i] * sv;
+            acc[s] += 1.0;
+            acc[3 + s] += 0.5 * mass[s] * (vx * vx + vy * vy + vz * vz);
+            if (s != 2) {
+                T ex, ey, ez;
+                gather<T>(g, E0, P.x[i], P.y[i], P.z[i], ex, ey, ez);
+                acc[6] += q[s] * (vx * (double)ex + vy * (double)ey + vz * (double)ez);
+            }
+        }
+    }
+    for (int k = 0; k < 7; ++k) {
+        double t = block_sum(acc[k], sh);
+        if (threadIdx.x == 0) part[blockIdx.x * 7 + k] = t;
+    }
+}
+
+__global__ void k_moments_final(const double* part, int nb, const int64_t* rho, int64_t nn, double* out) {
+    __shared__ double sh[kBlock / 64];
+    for (int k = 0; k < 7; ++k) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[b * 7 + k];
+        double t = block_sum(s, sh);
+        if (threadIdx.x == 0) out[k] = t;
+    }
+    __shared__ long long shl[kBlock / 64];
+    long long q = 0;
+    for (int64_t i = threadIdx.x; i < nn; i += blockDim.x) q += rho[i];
+    long long tq = block_sum(q, shl);
+    if (threadIdx.x == 0) ((long long*)out)[7] = tq;
+}
+
+hipError_t moments_phase(pic_ctx* c, double* out_dev) {
+    double sv = c->cfg.h / c->cfg.dt;
+    double* part = c->partials;
+    if (c->cfg.precision == PIC_F32)
+        hipLaunchKernelGGL(k_moments<float>, dim3(kMomBlocks), dim3(kBlock), 0, c->stream, species<float>(c, 0),
+                           species<float>(c, 1), species<float>(c, 2), (const float4*)c->buf.field0, c->g, sv,
+                           c->cfg.m_ion, c->st, part);
+    else
+        hipLaunchKernelGGL(k_moments<double>, dim3(kMomBlocks), dim3(kBlock), 0, c->stream, species<double>(c, 0),
+                           species<double>(c, 1), species<double>(c, 2), (const double4*)c->buf.field0, c->g, sv,
+                           c->cfg.m_ion, c->st, part);
+    hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(kBlock), 0, c->stream, part, kMomBlocks, c->buf.rho, c->g.nn,
+                       out_dev);
+    return hipGetLastError();
+}
+
+}  // namespace pic

@@ -1,0 +1,445 @@
+// pic_api.hip -- the extern "C" entry points declared in include/pic.h.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "pic_internal.hpp"
+
+using namespace pic;
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+pic_status fail(pic_ctx* c, pic_status code, const std::string& msg) {
+    if (c) {
+        c->err = msg;
+        if (code == PIC_E_HIP || code == PIC_E_CAPACITY || code == PIC_E_OVERFLOW) c->failed = code;
+    }
+    return code;
+}
+
+pic_status hip_check(pic_ctx* c, hipError_t e, const char* where) {
+    if (e == hipSuccess) return PIC_OK;
+    return fail(c, PIC_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+double adk_rate(double c, double e, double x32, double E) {
+    return c * std::pow(20.5 * x32 / E, e) * std::exp(-6.83 * x32 / E);
+}
+
+const char* check_config(const pic_config* cfg) {
+    if (!cfg) return "config is NULL";
+    if (cfg->nx < 4 || cfg->ny < 4 || cfg->nz < 4) return "nx, ny, nz must be >= 4";
+    if ((int64_t)cfg->nx * cfg->ny * cfg->nz >= (int64_t)1 << 31) return "grid too large";
+    if (!(cfg->h > 0) || !(cfg->dt > 0)) return "h and dt must be positive";
+    if (!(cfg->tip_r > 0) || !(cfg->tip_h >= cfg->tip_r)) return "need tip_r > 0 and tip_h >= tip_r";
+    double R = cfg->tip_r / cfg->h, H = cfg->tip_h / cfg->h;
+    if (R + 2.0 >= 0.5 * (cfg->nx - 1) || R + 2.0 >= 0.5 * (cfg->ny - 1) || H + 2.0 >= cfg->nz - 1)
+        return "the tip does not fit in the box with two spacings to spare";
+    if (cfg->precision != PIC_F64 && cfg->precision != PIC_F32) return "precision must be PIC_F64 or PIC_F32";
+    if (cfg->solver < PIC_SOLVER_CG || cfg->solver > PIC_SOLVER_MIXED) return "unknown solver";
+    if (cfg->xs_n < 2 || !cfg->xs_el || !cfg->xs_iz || !cfg->xs_cx) return "need three tables of >= 2 entries";
+    if (!(cfg->xs_emin > 0) || !(cfg->xs_emax > cfg->xs_emin)) return "need 0 < xs_emin < xs_emax";
+    for (int k = 0; k < cfg->xs_n; ++k)
+        if (!(cfg->xs_el[k] >= 0) || !(cfg->xs_iz[k] >= 0) || !(cfg->xs_cx[k] >= 0))
+            return "cross sections must be finite and >= 0";
+    if (cfg->fn_rings < 0 || cfg->fn_az < 0 || (cfg->fn_rings > 0) != (cfg->fn_az > 0))
+        return "fn_rings and fn_az must both be positive (or both 0: no emission)";
+    if (!(cfg->phi_w > 0) || !(cfg->xi > 0) || !(cfg->m_ion > 0)) return "phi_w, xi, m_ion must be positive";
+    if (!(cfg->laplace_rtol > 0) || !(cfg->step_rtol > 0) || cfg->step_maxit < 1) return "bad solver tolerances";
+    if (cfg->sort_every < 0) return "sort_every must be >= 0";
+    if (cfg->id_capacity < 0 || cfg->id_capacity > ((int64_t)1 << 32)) return "id_capacity out of range";
+    return nullptr;
+}
+
+int64_t id_capacity(const pic_config* cfg, const int64_t cap[3]) {
+    if (cfg->id_capacity > 0) return cfg->id_capacity;
+    int64_t v = 8 * (cap[0] + cap[1] + cap[2]) + (1 << 20);
+    return std::min<int64_t>(v, (int64_t)1 << 32);
+}
+
+__global__ void k_scale(double* y, const double* x, double a, int64_t n) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = a * x[i];
+}
+
+__global__ void k_init_state(DevState* st) {
+    memset(st, 0, sizeof(DevState));
+}
+
+}  // namespace
+
+size_t pic::scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[3], char* base) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> void* {
+        void* p = base ? (void*)(base + off) : nullptr;
+        off = align256(off + bytes);
+        return p;
+    };
+    int64_t nn = (int64_t)cfg->nx * cfg->ny * cfg->nz;
+    int64_t nc = (int64_t)(cfg->nx - 1) * (cfg->ny - 1) * (cfg->nz - 1);
+    int64_t capsum = cap[0] + cap[1] + cap[2];
+    int64_t capmax = std::max(cap[0], std::max(cap[1], cap[2]));
+    int64_t idc = id_capacity(cfg, cap);
+    int64_t words = (idc + 31) / 32;
+    size_t tsz = cfg->precision == PIC_F32 ? 4 : 8;
+    int64_t scan_n = std::max(nc + 1, std::max(capsum, words));
+    int64_t scan_blocks = (scan_n + 4095) / 4096 + 1;
+    int64_t parts = std::max<int64_t>(2 * ((nn + kBlock - 1) / kBlock), 7 * 512) + 64;
+    pic_ctx dummy;
+    pic_ctx* t = c ? c : &dummy;
+    t->st = (DevState*)take(sizeof(DevState));
+    t->dyn = (uint32_t*)take(64 * sizeof(uint32_t));
+    t->id_ptrs = (uint32_t**)take(3 * sizeof(uint32_t*));
+    t->mom_out = (double*)take(16 * sizeof(double));
+    t->xs = (double*)take(3 * (size_t)cfg->xs_n * sizeof(double));
+    t->cnt = (uint32_t*)take(nc * 4);
+    t->off = (uint32_t*)take((nc + 1) * 4);
+    for (int s = 0; s < 3; ++s) {
+        t->key[s] = (uint32_t*)take(cap[s] * 4);
+        t->slot[s] = (uint32_t*)take(cap[s] * 4);
+    }
+    t->bins = (uint32_t*)take(capsum * 4);
+    t->big = (uint32_t*)take(nc * 4);
+    t->fi_list = (uint32_t*)take(cap[2] * 4);
+    t->nflag = (uint32_t*)take(cap[2] * 4);
+    t->prod_list = (uint32_t*)take(cap[2] * 4);
+    t->prod_ev = (int32_t*)take(cap[2] * 4);
+    t->prod_ve = (double*)take(cap[2] * 3 * 8);
+    for (int k = 0; k < 2; ++k) {
+        t->bitmap[k] = (uint32_t*)take(words * 4);
+        t->bm_prefix[k] = (uint32_t*)take(words * 4);
+    }
+    t->ev = (pic_event*)take(cap[2] * sizeof(pic_event));
+    t->scan_blocks = (uint32_t*)take(scan_blocks * 4);
+    t->rank_flag = (uint32_t*)take(capsum * 4);
+    t->rank = (uint32_t*)take(capsum * 4);
+    t->tmp = take(capmax * (6 * tsz + 4));
+    t->cg_r = (double*)take(nn * 8);
+    t->cg_p0 = (double*)take(nn * 8);
+    t->cg_p1 = (double*)take(nn * 8);
+    t->cg_q = (double*)take(nn * 8);
+    t->partials = (double*)take(parts * 8);
+    t->mg = take(mg_bytes(cfg));
+    if (c) {
+        c->scan_blocks_n = scan_blocks;
+        c->partials_n = parts;
+        c->tmp_cap = capmax;
+        c->ev_cap = cap[2];
+        c->id_cap = idc;
+        c->bm_words = words;
+    }
+    return off + 256;
+}
+
+extern "C" {
+
+pic_status pic_scratch_size(const pic_config* cfg, const int64_t cap[3], size_t* bytes) {
+    if (const char* e = check_config(cfg)) {
+        (void)e;
+        return PIC_E_INVALID_ARG;
+    }
+    if (!cap || !bytes) return PIC_E_INVALID_ARG;
+    for (int s = 0; s < 3; ++s)
+        if (cap[s] < 0 || cap[s] >= ((int64_t)1 << 30)) return PIC_E_INVALID_ARG;
+    *bytes = scratch_layout(nullptr, cfg, cap, nullptr);
+    return PIC_OK;
+}
+
+static thread_local std::string g_init_error;
+
+pic_status pic_init(const pic_config* cfg, const pic_buffers* bufs, void* hip_stream, pic_ctx** out) {
+    if (!out) return PIC_E_INVALID_ARG;
+    *out = nullptr;
+    if (const char* e = check_config(cfg)) {
+        g_init_error = e;
+        return PIC_E_INVALID_ARG;
+    }
+    if (!bufs) return PIC_E_INVALID_ARG;
+    for (int s = 0; s < 3; ++s) {
+        if (bufs->cap[s] < 0 || bufs->cap[s] >= ((int64_t)1 << 30)) return PIC_E_INVALID_ARG;
+        if (bufs->cap[s] > 0 && (!bufs->x[s] || !bufs->y[s] || !bufs->z[s] || !bufs->vx[s] || !bufs->vy[s] ||
+                                 !bufs->vz[s] || !bufs->id[s]))
+            return PIC_E_INVALID_ARG;
+    }
+    if (!bufs->phi || !bufs->phi1 || !bufs->rho || !bufs->field || !bufs->field0 || !bufs->node_type || !bufs->scratch)
+        return PIC_E_INVALID_ARG;
+    if (((uintptr_t)bufs->scratch) % 256 != 0) return PIC_E_INVALID_ARG;
+    size_t need = scratch_layout(nullptr, cfg, bufs->cap, nullptr);
+    if (bufs->scratch_bytes < need) {
+        g_init_error = "scratch too small";
+        return PIC_E_INVALID_ARG;
+    }
+    pic_ctx* c = new (std::nothrow) pic_ctx();
+    if (!c) return PIC_E_INVALID_ARG;
+    c->cfg = *cfg;
+    c->cfg.xs_el = c->cfg.xs_iz = c->cfg.xs_cx = nullptr;
+    c->buf = *bufs;
+    c->stream = (hipStream_t)hip_stream;
+    scratch_layout(c, cfg, bufs->cap, (char*)bufs->scratch);
+    Grid& g = c->g;
+    g.nx = cfg->nx;
+    g.ny = cfg->ny;
+    g.nz = cfg->nz;
+    g.h = cfg->h;
+    g.R = cfg->tip_r / cfg->h;
+    g.H = cfg->tip_h / cfg->h;
+    g.zc = g.H - g.R;
+    g.xc = 0.5 * (double)(cfg->nx - 1);
+    g.yc = 0.5 * (double)(cfg->ny - 1);
+    g.nn = (int64_t)cfg->nx * cfg->ny * cfg->nz;
+    g.nc = (int64_t)(cfg->nx - 1) * (cfg->ny - 1) * (cfg->nz - 1);
+    const double qm[3] = {-kQe / kMe, kQe / cfg->m_ion, 0.0};
+    for (int s = 0; s < 3; ++s) c->kq[s] = qm[s] * cfg->dt * cfg->dt / cfg->h;
+    // ADK constants of Eq. dfi (z = 1) and the field below which P dt < 2^-64
+    c->adk_n = 3.69 / std::sqrt(cfg->xi);
+    c->adk_c = 1.52 * std::pow(4.0, c->adk_n) * cfg->xi / (c->adk_n * std::tgamma(2.0 * c->adk_n));
+    c->ebsi = 1.5 * std::pow(cfg->xi, 1.5);
+    {
+        double x32 = std::pow(cfg->xi, 1.5), e = 2.0 * c->adk_n - 1.0, dtfs = cfg->dt * 1e15;
+        double lo = 1e-6, hi = c->ebsi;
+        if (adk_rate(c->adk_c, e, x32, hi) * dtfs < 0x1p-64) {
+            c->fi_thr = hi;
+        } else {
+            for (int it = 0; it < 200; ++it) {
+                double mid = 0.5 * (lo + hi);
+                if (adk_rate(c->adk_c, e, x32, mid) * dtfs < 0x1p-64) lo = mid;
+                else hi = mid;
+            }
+            c->fi_thr = lo;
+        }
+    }
+    double mel = 0, miz = 0, mcx = 0;
+    for (int k = 0; k < cfg->xs_n; ++k) {
+        mel = std::max(mel, cfg->xs_el[k]);
+        miz = std::max(miz, cfg->xs_iz[k]);
+        mcx = std::max(mcx, cfg->xs_cx[k]);
+    }
+    c->xs_max[0] = mel + miz;
+    c->xs_max[1] = mcx;
+    c->npatch = 0;
+    if (cfg->fn_rings > 0) c->npatch = ((int64_t)cfg->fn_rings + (int64_t)std::ceil(g.zc)) * cfg->fn_az;
+
+    pic_status st = PIC_OK;
+    auto H = [&](hipError_t e, const char* w) {
+        if (st == PIC_OK) st = hip_check(c, e, w);
+    };
+    H(hipHostMalloc((void**)&c->host_st, sizeof(DevState) + 256, hipHostMallocDefault), "hipHostMalloc");
+    if (st != PIC_OK) {
+        g_init_error = c->err;
+        delete c;
+        return st;
+    }
+    hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, c->stream, c->st);
+    H(hipMemcpyAsync(c->xs, cfg->xs_el, cfg->xs_n * 8, hipMemcpyHostToDevice, c->stream), "copy tables");
+    H(hipMemcpyAsync(c->xs + cfg->xs_n, cfg->xs_iz, cfg->xs_n * 8, hipMemcpyHostToDevice, c->stream), "copy tables");
+    H(hipMemcpyAsync(c->xs + 2 * cfg->xs_n, cfg->xs_cx, cfg->xs_n * 8, hipMemcpyHostToDevice, c->stream),
+      "copy tables");
+    uint32_t* ids[3] = {bufs->id[0], bufs->id[1], bufs->id[2]};
+    H(hipMemcpyAsync(c->id_ptrs, ids, sizeof(ids), hipMemcpyHostToDevice, c->stream), "copy id pointers");
+    H(launch_zero(c->dyn, 64 * 4, c->stream), "zero");
+    H(launch_zero(c->cnt, g.nc * 4, c->stream), "zero");
+    H(launch_zero(c->nflag, bufs->cap[2] * 4, c->stream), "zero");
+    for (int k = 0; k < 2; ++k) H(launch_zero(c->bitmap[k], c->bm_words * 4, c->stream), "zero");
+    H(launch_zero(bufs->rho, g.nn * 8, c->stream), "zero");
+    H(launch_node_types(c), "node types");
+    // unit-anode Laplace problem: phi1, its field (Shockley-Ramo weighting
+    // field) and the anode voltage that gives the requested apex field
+    pic_solve_info info{};
+    if (st == PIC_OK) {
+        int r = cg_solve(c, bufs->phi1, 1.0, bufs->rho, PIC_GUESS_ZERO, cfg->laplace_rtol, 1000000, &info);
+        if (r != 0) st = fail(c, PIC_E_HIP, "Laplace solve failed");
+        else if (!info.converged) st = fail(c, PIC_E_NOT_CONVERGED, "Laplace solve did not converge");
+    }
+    if (st == PIC_OK) {
+        H(apex_interp(c, bufs->phi1, g.xc, g.yc, g.H + 1.0, c->mom_out), "apex");
+        double v = 0.0;
+        H(hipMemcpyAsync(&v, c->mom_out, 8, hipMemcpyDeviceToHost, c->stream), "apex copy");
+        H(hipStreamSynchronize(c->stream), "sync");
+        c->F1 = v / cfg->h;
+        if (!(c->F1 > 0)) st = fail(c, PIC_E_INVALID_ARG, "non-positive Laplace apex field");
+        else c->V0 = cfg->apex_field / c->F1;
+    }
+    if (st == PIC_OK) {
+        H(launch_field(c, bufs->phi1, bufs->field0), "field0");
+        int64_t G = (g.nn + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL(k_scale, dim3((unsigned)G), dim3(kBlock), 0, c->stream, bufs->phi, bufs->phi1, c->V0, g.nn);
+        H(launch_field(c, bufs->phi, bufs->field), "field");
+        H(hipStreamSynchronize(c->stream), "sync");
+    }
+    if (st != PIC_OK) {
+        g_init_error = c->err;
+        (void)hipHostFree(c->host_st);
+        delete c;
+        return st;
+    }
+    c->last_solve = info;
+    *out = c;
+    return PIC_OK;
+}
+
+static pic_status sync_state(pic_ctx* c) {
+    pic_status s = hip_check(c, hipMemcpyAsync(c->host_st, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream),
+                             "state copy");
+    if (s != PIC_OK) return s;
+    s = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    if (s != PIC_OK) return s;
+    if (c->host_st->error != 0) {
+        int e = c->host_st->error;
+        return fail(c, e, e == PIC_E_CAPACITY ? "particle capacity exceeded (or a cell holds more than 4096 particles)"
+                                               : "device error");
+    }
+    return PIC_OK;
+}
+
+pic_status pic_inject(pic_ctx* c, const pic_particles* src, int64_t* n_added) {
+    if (!c) return PIC_E_INVALID_ARG;
+    if (c->failed) return PIC_E_STATE;
+    if (n_added) *n_added = 0;
+    pic_status s = sync_state(c);
+    if (s != PIC_OK) return s;
+    if (src) {
+        if (src->species < 0 || src->species > 2 || src->n < 0) return fail(c, PIC_E_INVALID_ARG, "bad particle load");
+        if (src->n > 0 && (!src->x || !src->y || !src->z || !src->vx || !src->vy || !src->vz))
+            return fail(c, PIC_E_INVALID_ARG, "NULL particle array");
+        if ((int64_t)c->host_st->n_slots[src->species] + src->n > c->buf.cap[src->species])
+            return fail(c, PIC_E_CAPACITY, "particle capacity exceeded by the load");
+        s = hip_check(c, load_particles(c, src), "load");
+        if (s != PIC_OK) return s;
+        s = sync_state(c);
+        if (s == PIC_OK && n_added) *n_added = src->n;
+        c->bins_valid = 0;
+        return s;
+    }
+    unsigned long long before = c->host_st->injected;
+    s = hip_check(c, inject_phase(c), "inject");
+    if (s != PIC_OK) return s;
+    s = sync_state(c);
+    if (s == PIC_OK && n_added) *n_added = (int64_t)(c->host_st->injected - before);
+    c->bins_valid = 0;
+    return s;
+}
+
+static pic_status solve(pic_ctx* c, int solver, int guess, double rtol, int maxit, pic_solve_info* info) {
+    pic_solve_info tmp{};
+    if (!info) info = &tmp;
+    int r;
+    if (solver == PIC_SOLVER_CG)
+        r = cg_solve(c, c->buf.phi, c->V0, c->buf.rho, guess, rtol, maxit, info);
+    else if (solver == PIC_SOLVER_MGCG)
+        r = mgcg_solve(c, c->buf.phi, c->V0, c->buf.rho, guess, rtol, maxit, info);
+    else
+        r = mixed_solve(c, c->buf.phi, c->V0, c->buf.rho, guess, rtol, maxit, info);
+    if (r == -3) return fail(c, PIC_E_INVALID_ARG, "solver not available for this configuration");
+    if (r != 0) return fail(c, PIC_E_HIP, "solver failed");
+    c->last_solve = *info;
+    pic_status s = hip_check(c, launch_field(c, c->buf.phi, c->buf.field), "field");
+    if (s != PIC_OK) return s;
+    if (!info->converged) return fail(c, PIC_E_NOT_CONVERGED, "Poisson solve did not converge");
+    return PIC_OK;
+}
+
+pic_status pic_step(pic_ctx* c, int32_t nsteps, uint32_t flags) {
+    if (!c) return PIC_E_INVALID_ARG;
+    if (c->failed) return PIC_E_STATE;
+    if (nsteps < 0) return fail(c, PIC_E_INVALID_ARG, "nsteps < 0");
+    pic_status result = PIC_OK;
+    for (int32_t n = 0; n < nsteps; ++n) {
+        pic_status s = PIC_OK;
+        if (flags & PIC_STEP_INJECT) s = hip_check(c, inject_phase(c), "inject");
+        if (s == PIC_OK && (flags & (PIC_STEP_PUSH | PIC_STEP_DEPOSIT)))
+            s = hip_check(c, particles_phase(c, (flags & PIC_STEP_PUSH) != 0), "push");
+        if (s == PIC_OK && (flags & PIC_STEP_COLLIDE)) {
+            if (!c->bins_valid) return fail(c, PIC_E_INVALID_ARG, "the collide phase needs a push or deposit phase first");
+            s = hip_check(c, collide_phase(c, (flags & PIC_STEP_EVENTS) != 0), "collide");
+        }
+        if (s == PIC_OK && (flags & PIC_STEP_SOLVE)) {
+            s = solve(c, c->cfg.solver, PIC_GUESS_PREVIOUS, c->cfg.step_rtol, c->cfg.step_maxit, nullptr);
+            if (s == PIC_E_NOT_CONVERGED) {
+                result = s;
+                s = PIC_OK;
+            }
+        } else if (s == PIC_OK && (flags & PIC_STEP_FIELD)) {
+            s = hip_check(c, launch_field(c, c->buf.phi, c->buf.field), "field");
+        }
+        if (s != PIC_OK) return s;
+        if (flags & PIC_STEP_ADVANCE) c->step++;
+    }
+    return result;
+}
+
+pic_status pic_solve_poisson(pic_ctx* c, int32_t solver, int32_t guess, double rtol, int32_t maxit,
+                             pic_solve_info* info) {
+    if (!c) return PIC_E_INVALID_ARG;
+    if (c->failed) return PIC_E_STATE;
+    if (solver < PIC_SOLVER_CG || solver > PIC_SOLVER_MIXED || (guess != PIC_GUESS_ZERO && guess != PIC_GUESS_PREVIOUS) ||
+        !(rtol > 0) || maxit < 0)
+        return fail(c, PIC_E_INVALID_ARG, "bad solver arguments");
+    return solve(c, solver, guess, rtol, maxit, info);
+}
+
+pic_status pic_moments(pic_ctx* c, pic_moments_t* out) {
+    if (!c || !out) return PIC_E_INVALID_ARG;
+    if (c->failed) return PIC_E_STATE;
+    pic_status s = hip_check(c, moments_phase(c, c->mom_out), "moments");
+    if (s != PIC_OK) return s;
+    double host[8];
+    s = hip_check(c, hipMemcpyAsync(host, c->mom_out, sizeof(host), hipMemcpyDeviceToHost, c->stream), "copy");
+    if (s != PIC_OK) return s;
+    s = sync_state(c);
+    std::memset(out, 0, sizeof(*out));
+    const DevState* h = c->host_st;
+    for (int k = 0; k < 3; ++k) {
+        out->n_alive[k] = (int64_t)llround(host[k]);
+        out->n_slots[k] = (int64_t)h->n_slots[k];
+        out->ke[k] = host[3 + k];
+        for (int b = 0; b < 5; ++b) out->absorbed[k][b] = (int64_t)h->absorbed[k][b];
+    }
+    for (int k = 0; k < 5; ++k) out->events[k] = (int64_t)h->events[k];
+    out->injected = (int64_t)h->injected;
+    out->fn_clamped = (int64_t)h->fn_clamped;
+    out->bsi_count = (int64_t)h->bsi_count;
+    long long q;
+    std::memcpy(&q, &host[7], 8);
+    out->q_total = q;
+    out->next_id = (int64_t)h->next_id;
+    out->step = c->step;
+    out->i_sr = host[6];
+    out->fn_expected = h->fn_expected;
+    out->v0 = c->V0;
+    out->apex_field1 = c->F1;
+    out->error = h->error;
+    return s;
+}
+
+pic_status pic_events(pic_ctx* c, pic_event* out, int64_t cap, int64_t* n) {
+    if (!c || !n || cap < 0 || (cap > 0 && !out)) return PIC_E_INVALID_ARG;
+    if (c->failed) return PIC_E_STATE;
+    pic_status s = sync_state(c);
+    if (s != PIC_OK) return s;
+    int64_t have = std::min<int64_t>((int64_t)c->host_st->n_ev, c->ev_cap);
+    *n = have;
+    int64_t m = std::min(have, cap);
+    if (m > 0) {
+        s = hip_check(c, hipMemcpyAsync(out, c->ev, m * sizeof(pic_event), hipMemcpyDeviceToHost, c->stream), "copy");
+        if (s == PIC_OK) s = hip_check(c, hipStreamSynchronize(c->stream), "sync");
+    }
+    return s;
+}
+
+const char* pic_last_error(const pic_ctx* c) {
+    if (!c) return g_init_error.c_str();
+    return c->err.c_str();
+}
+
+void pic_destroy(pic_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    if (c->host_st) (void)hipHostFree(c->host_st);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,251 @@
+// pic_internal.hpp -- types and device helpers shared by the libpic kernels.
+//
+// Particle state is SoA per species in grid units (X = x/h, V = v dt/h);
+// node arrays are x-fastest, index n = (k*ny + j)*nx + i; cell (i,j,k) spans
+// nodes i..i+1, j..j+1, k..k+1 and has index (k*(ny-1) + j)*(nx-1) + i.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "pic.h"
+
+namespace pic {
+
+// CODATA 2022 (SI).
+constexpr double kQe = 1.602176634e-19;
+constexpr double kMe = 9.1093837139e-31;
+constexpr double kEps0 = 8.8541878188e-12;
+constexpr double kHpl = 6.62607015e-34;
+constexpr double kPi = 3.14159265358979323846;
+
+constexpr uint32_t kDead = 0xFFFFFFFFu;      // id of a free slot, key of a removed particle
+constexpr int kSmallCell = 16;                // cells up to this many particles: one thread each
+constexpr int kBigCell = 4096;                // cells up to this many: one wavefront each
+constexpr int kBlock = 256;
+
+// Third Philox counter word: purpose of the draw.
+constexpr uint32_t kTagMcc1 = 1, kTagMcc2 = 2, kTagPair1 = 3, kTagPair2 = 4, kTagFi = 5, kTagInj = 6;
+
+// Device-resident counters and scalars of one context.
+struct DevState {
+    unsigned long long n_slots[3];
+    unsigned long long n_push[3];      // slots covered by the bins of the last push/deposit
+    unsigned long long next_id;
+    unsigned long long absorbed[3][5];
+    unsigned long long events[5];
+    unsigned long long injected, fn_clamped, bsi_count;
+    unsigned long long n_fi, n_prod, n_prod_kind[2], n_ev, n_big;
+    unsigned long long n_sorted[3];
+    double fn_expected;
+    unsigned int smax_bits[3];         // max |V| per species (float bits, rounded up)
+    int error;
+    // CG scalars
+    double rr, bb, rr0, pq, alpha, beta, rtol;
+    int it, maxit, done, zero_solution;
+    unsigned int red_count;
+    // mixed-precision refinement
+    double rr_outer;
+};
+
+struct Grid {
+    int nx, ny, nz;
+    double h, R, H, zc, xc, yc;
+    int64_t nn, nc;
+};
+
+template <typename T>
+struct Species {
+    T *x, *y, *z, *vx, *vy, *vz;
+    uint32_t* id;
+    int64_t cap;
+};
+
+template <typename T>
+struct V4 {};
+template <>
+struct V4<float> { using type = float4; };
+template <>
+struct V4<double> { using type = double4; };
+
+// ---------------------------------------------------------------------------
+// Device helpers
+
+// Philox4x32-10 (Salmon et al., SC'11).
+__device__ inline void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
+        uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
+        uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+// Uniform in (0,1) from 52 bits: (k + 1/2) 2^-52, exact in FP64.
+__device__ inline double u52(uint32_t hi, uint32_t lo) {
+    uint64_t k = ((uint64_t)hi << 20) | (uint64_t)(lo >> 12);
+    return ((double)k + 0.5) * 0x1p-52;
+}
+
+struct Draw2 { double a, b; };
+
+__device__ inline Draw2 draw2(uint64_t seed, uint32_t w0, uint32_t step, uint32_t tag, uint32_t sub) {
+    uint32_t c[4] = {w0, step, tag, sub};
+    philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    return {u52(c[0], c[1]), u52(c[2], c[3])};
+}
+
+__device__ inline bool inside_tip(const Grid& g, double X, double Y, double Z) {
+    double dx = X - g.xc, dy = Y - g.yc;
+    double rho2 = dx * dx + dy * dy;
+    if (Z < 0.0) return false;
+    if (Z <= g.zc) return rho2 <= g.R * g.R;
+    double dz = Z - g.zc;
+    return rho2 + dz * dz <= g.R * g.R;
+}
+
+// 0 inside the vacuum region, else the boundary a particle left through:
+// 1 cathode plane, 2 anode plane, 3 lateral faces (also non-finite), 4 tip.
+__device__ inline int boundary_code(const Grid& g, double X, double Y, double Z) {
+    if (Z <= 0.0) return 1;
+    if (Z >= (double)(g.nz - 1)) return 2;
+    bool in = (X >= 0.0) && (X < (double)(g.nx - 1)) && (Y >= 0.0) && (Y < (double)(g.ny - 1)) &&
+              (Z > 0.0) && (Z < (double)(g.nz - 1));
+    if (!in) return 3;
+    if (inside_tip(g, X, Y, Z)) return 4;
+    return 0;
+}
+
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// CIC weight of one axis quantized to 2^-bits, rounded half up (exact).
+__device__ inline int64_t quantize(double f, int bits) {
+    double t = ldexp(f, bits);
+    double fl = floor(t);
+    int64_t q = (int64_t)fl;
+    if (t - fl >= 0.5) q += 1;
+    return q;
+}
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+// Remap a block index so that consecutive chunks of the index space land on
+// one XCD (blocks are dispatched round-robin over the 8 XCDs).
+__device__ inline int64_t xcd_block(int64_t b, int64_t G) {
+    int64_t per = G / 8, rem = G % 8;
+    int64_t x = b % 8, t = b / 8;
+    return x * per + (x < rem ? x : rem) + t;
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block-wide sum in a fixed order (deterministic): wave sums then the first
+// wave adds the wave results in index order.
+template <typename T>
+__device__ inline T block_sum(T v, T* sh) {
+    v = wave_sum(v);
+    int w = threadIdx.x / 64, l = threadIdx.x % 64;
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    T r = T(0);
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < (int)(blockDim.x + 63) / 64; ++i) r += sh[i];
+    }
+    __syncthreads();
+    return r;  // valid in thread 0
+}
+
+}  // namespace pic
+
+// ---------------------------------------------------------------------------
+// The context (host side).
+struct pic_ctx {
+    pic_config cfg;
+    pic_buffers buf;
+    hipStream_t stream;
+    pic::Grid g;
+    double V0 = 0.0, F1 = 0.0;
+    double kq[3];                 // kick per step in grid units per V/m
+    double adk_c = 0.0, adk_n = 0.0, fi_thr = 0.0, ebsi = 0.0;
+    double xs_max[2];             // max total cross section per pair class [m^2]
+    int64_t npatch = 0;
+    int64_t id_cap = 0, bm_words = 0;
+    // scratch carve
+    pic::DevState* st = nullptr;
+    double* xs = nullptr;         // 3 * xs_n
+    uint32_t* cnt = nullptr;      // nc
+    uint32_t* off = nullptr;      // nc + 1
+    uint32_t* key[3] = {};
+    uint32_t* slot[3] = {};
+    uint32_t* bins = nullptr;     // sum cap
+    uint32_t* big = nullptr;      // big-cell list (nc)
+    uint32_t* fi_list = nullptr;  // cap neutral
+    uint32_t* nflag = nullptr;    // cap neutral: step+1 if the neutral had an event
+    uint32_t* prod_list = nullptr;
+    int32_t* prod_ev = nullptr;
+    double* prod_ve = nullptr;    // 3 * cap neutral
+    uint32_t* bitmap[2] = {};
+    uint32_t* bm_prefix[2] = {};
+    pic_event* ev = nullptr;
+    int64_t ev_cap = 0;
+    uint32_t* scan_blocks = nullptr;
+    int64_t scan_blocks_n = 0;
+    uint32_t* dyn = nullptr;      // small device-side counts (scan lengths and totals)
+    uint32_t** id_ptrs = nullptr; // device copy of the three id array pointers
+    uint32_t* rank_flag = nullptr;
+    uint32_t* rank = nullptr;     // reorder destination ranks (per bin entry)
+    void* tmp = nullptr;          // reorder staging: 6 arrays of tmp_cap elements + ids
+    int64_t tmp_cap = 0;
+    double* mom_out = nullptr;
+    double *cg_r = nullptr, *cg_p0 = nullptr, *cg_p1 = nullptr, *cg_q = nullptr;
+    double* partials = nullptr;
+    int64_t partials_n = 0;
+    void* mg = nullptr;           // multigrid hierarchy (pic_mg.hip)
+    void* mixed = nullptr;        // mixed-precision vectors
+    // host state
+    pic::DevState* host_st = nullptr;  // pinned mirror
+    int64_t step = 0;
+    int bins_valid = 0, bins_dirty = 0;
+    int64_t collide_count = 0;
+    int failed = 0;
+    std::string err;
+    pic_solve_info last_solve{};
+};
+
+namespace pic {
+size_t scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[3], char* base);
+hipError_t launch_node_types(pic_ctx* c);
+hipError_t launch_field(pic_ctx* c, const double* phi, void* field);
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
+int cg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess, double rtol, int maxit,
+             pic_solve_info* info);
+int mg_setup(pic_ctx* c);
+int mgcg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess, double rtol, int maxit,
+               pic_solve_info* info);
+int mixed_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess, double rtol, int maxit,
+                pic_solve_info* info);
+size_t mg_bytes(const pic_config* cfg);
+hipError_t scan_u32(pic_ctx* c, const uint32_t* in, uint32_t* out, int64_t n_max, const uint32_t* nd,
+                    uint32_t* total, bool zero_in, bool popcount);
+hipError_t particles_phase(pic_ctx* c, bool move);
+hipError_t collide_phase(pic_ctx* c, bool record);
+hipError_t inject_phase(pic_ctx* c);
+hipError_t load_particles(pic_ctx* c, const pic_particles* src);
+hipError_t moments_phase(pic_ctx* c, double* out_dev);
+hipError_t apex_interp(pic_ctx* c, const double* phi, double X, double Y, double Z, double* out_dev);
+}  // namespace pic

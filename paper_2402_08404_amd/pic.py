@@ -1,0 +1,312 @@
+"""Thin Python binding of libpic (include/pic.h).
+
+The functions ``pic_*`` below have the names and arguments of the C entry
+points and only marshal arguments; every step of the computation runs in the
+HIP kernels of libpic. PyTorch is used for device memory (all buffers are
+torch tensors owned by :class:`Simulation`) and for the HIP stream.
+
+libpic must be built (``paper_2402_08404_amd.build.build()``); importing this
+module on a machine without it raises, there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime libpic links against)
+
+from . import workloads
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpic.so")
+
+PIC_OK = 0
+ERRORS = {-1: "INVALID_ARG", -2: "HIP", -3: "CAPACITY", -4: "OVERFLOW", -5: "NOT_CONVERGED", -6: "STATE"}
+PIC_F64, PIC_F32 = 0, 1
+PIC_SOLVER_CG, PIC_SOLVER_MGCG, PIC_SOLVER_MIXED = 0, 1, 2
+PIC_GUESS_ZERO, PIC_GUESS_PREVIOUS = 0, 1
+STEP_INJECT, STEP_PUSH, STEP_DEPOSIT, STEP_COLLIDE = 0x01, 0x02, 0x04, 0x08
+STEP_SOLVE, STEP_FIELD, STEP_ADVANCE, STEP_EVENTS = 0x10, 0x20, 0x40, 0x80
+STEP_FULL = STEP_INJECT | STEP_PUSH | STEP_COLLIDE | STEP_SOLVE | STEP_ADVANCE
+DEAD = 0xFFFFFFFF
+
+
+class PicError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libpic error {code} ({ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class pic_config(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("precision", C.c_int32),
+                ("h", C.c_double), ("tip_r", C.c_double), ("tip_h", C.c_double), ("apex_field", C.c_double),
+                ("phi_w", C.c_double), ("dt", C.c_double), ("xi", C.c_double), ("m_ion", C.c_double),
+                ("seed", C.c_uint64), ("xs_n", C.c_int32), ("solver", C.c_int32),
+                ("xs_emin", C.c_double), ("xs_emax", C.c_double),
+                ("xs_el", C.POINTER(C.c_double)), ("xs_iz", C.POINTER(C.c_double)), ("xs_cx", C.POINTER(C.c_double)),
+                ("fn_rings", C.c_int32), ("fn_az", C.c_int32), ("laplace_rtol", C.c_double),
+                ("step_rtol", C.c_double), ("step_maxit", C.c_int32), ("sort_every", C.c_int32),
+                ("id_capacity", C.c_int64)]
+
+
+class pic_buffers(C.Structure):
+    _fields_ = [(k, C.c_void_p * 3) for k in ("x", "y", "z", "vx", "vy", "vz")] + \
+               [("id", C.c_void_p * 3), ("cap", C.c_int64 * 3), ("phi", C.c_void_p), ("phi1", C.c_void_p),
+                ("rho", C.c_void_p), ("field", C.c_void_p), ("field0", C.c_void_p), ("node_type", C.c_void_p),
+                ("scratch", C.c_void_p), ("scratch_bytes", C.c_size_t)]
+
+
+class pic_particles(C.Structure):
+    _fields_ = [("species", C.c_int32), ("pad", C.c_int32), ("n", C.c_int64)] + \
+               [(k, C.c_void_p) for k in ("x", "y", "z", "vx", "vy", "vz")]
+
+
+class pic_solve_info(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("relres", C.c_double), ("relres0", C.c_double)]
+
+
+class pic_moments_t(C.Structure):
+    _fields_ = [("n_alive", C.c_int64 * 3), ("n_slots", C.c_int64 * 3), ("absorbed", (C.c_int64 * 5) * 3),
+                ("events", C.c_int64 * 5), ("injected", C.c_int64), ("fn_clamped", C.c_int64),
+                ("bsi_count", C.c_int64), ("q_total", C.c_int64), ("next_id", C.c_int64), ("step", C.c_int64),
+                ("ke", C.c_double * 3), ("i_sr", C.c_double), ("fn_expected", C.c_double), ("v0", C.c_double),
+                ("apex_field1", C.c_double), ("error", C.c_int32), ("pad", C.c_int32)]
+
+
+class pic_event(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("id_a", C.c_uint32), ("id_b", C.c_uint32), ("new_ion", C.c_uint32),
+                ("new_e", C.c_uint32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpic.so (after torch, so that both share one HIP runtime)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run paper_2402_08404_amd.build.build()")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.pic_scratch_size.argtypes = [C.POINTER(pic_config), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]
+        L.pic_init.argtypes = [C.POINTER(pic_config), C.POINTER(pic_buffers), vp, C.POINTER(vp)]
+        L.pic_inject.argtypes = [vp, C.POINTER(pic_particles), C.POINTER(C.c_int64)]
+        L.pic_step.argtypes = [vp, C.c_int32, C.c_uint32]
+        L.pic_solve_poisson.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_int32, C.POINTER(pic_solve_info)]
+        L.pic_moments.argtypes = [vp, C.POINTER(pic_moments_t)]
+        L.pic_events.argtypes = [vp, C.POINTER(pic_event), C.c_int64, C.POINTER(C.c_int64)]
+        L.pic_last_error.argtypes = [vp]
+        L.pic_last_error.restype = C.c_char_p
+        L.pic_destroy.argtypes = [vp]
+        L.pic_destroy.restype = None
+        for f in ("pic_scratch_size", "pic_init", "pic_inject", "pic_step", "pic_solve_poisson", "pic_moments",
+                  "pic_events"):
+            getattr(L, f).restype = C.c_int32
+        _lib = L
+    return _lib
+
+
+def _check(code: int, ctx=None):
+    if code != PIC_OK:
+        msg = lib().pic_last_error(ctx)
+        raise PicError(code, msg.decode() if msg else "")
+
+
+# --------------------------------------------------------------------------
+# Entry points (same names as the C ABI)
+
+
+def pic_scratch_size(cfg: pic_config, cap) -> int:
+    n = C.c_size_t()
+    _check(lib().pic_scratch_size(C.byref(cfg), (C.c_int64 * 3)(*cap), C.byref(n)))
+    return n.value
+
+
+def pic_init(cfg: pic_config, bufs: pic_buffers, stream: int):
+    ctx = C.c_void_p()
+    _check(lib().pic_init(C.byref(cfg), C.byref(bufs), C.c_void_p(stream), C.byref(ctx)))
+    return ctx
+
+
+def pic_inject(ctx, src: pic_particles | None) -> int:
+    n = C.c_int64()
+    _check(lib().pic_inject(ctx, C.byref(src) if src is not None else None, C.byref(n)), ctx)
+    return n.value
+
+
+def pic_step(ctx, nsteps: int, flags: int) -> int:
+    code = lib().pic_step(ctx, nsteps, flags)
+    if code not in (PIC_OK, -5):
+        _check(code, ctx)
+    return code
+
+
+def pic_solve_poisson(ctx, solver: int, guess: int, rtol: float, maxit: int, allow_unconverged: bool = False) -> dict:
+    info = pic_solve_info()
+    code = lib().pic_solve_poisson(ctx, solver, guess, rtol, maxit, C.byref(info))
+    if code != PIC_OK and not (allow_unconverged and code == -5):
+        _check(code, ctx)
+    return {"iterations": info.iterations, "converged": bool(info.converged), "relres": info.relres,
+            "relres0": info.relres0}
+
+
+def pic_moments(ctx) -> dict:
+    m = pic_moments_t()
+    _check(lib().pic_moments(ctx, C.byref(m)), ctx)
+    return {"n_alive": np.array(m.n_alive[:]), "n_slots": np.array(m.n_slots[:]),
+            "absorbed": np.array([list(r) for r in m.absorbed]), "events": np.array(m.events[:]),
+            "injected": m.injected, "fn_clamped": m.fn_clamped, "bsi_count": m.bsi_count, "q_total": m.q_total,
+            "next_id": m.next_id, "step": m.step, "ke": np.array(m.ke[:]), "i_sr": m.i_sr,
+            "fn_expected": m.fn_expected, "v0": m.v0, "apex_field1": m.apex_field1, "error": m.error}
+
+
+def pic_events(ctx, cap: int) -> list:
+    buf = (pic_event * max(cap, 1))()
+    n = C.c_int64()
+    _check(lib().pic_events(ctx, buf, cap, C.byref(n)), ctx)
+    m = min(n.value, cap)
+    return [(buf[i].kind, buf[i].id_a, buf[i].id_b, buf[i].new_ion, buf[i].new_e) for i in range(m)]
+
+
+def pic_last_error(ctx) -> str:
+    s = lib().pic_last_error(ctx)
+    return s.decode() if s else ""
+
+
+def pic_destroy(ctx):
+    lib().pic_destroy(ctx)
+
+
+# --------------------------------------------------------------------------
+# Memory plumbing: one instance with torch-owned device buffers
+
+
+def make_config(cfg: workloads.Config, precision=PIC_F64, solver=PIC_SOLVER_CG, laplace_rtol=1e-13,
+                step_rtol=1e-8, step_maxit=20000, sort_every=16, id_capacity=0):
+    keep = [np.ascontiguousarray(t, dtype=np.float64) for t in (cfg.xs_el, cfg.xs_iz, cfg.xs_cx)]
+    dp = C.POINTER(C.c_double)
+    c = pic_config(nx=cfg.nx, ny=cfg.ny, nz=cfg.nz, precision=precision, h=cfg.h, tip_r=cfg.tip_r,
+                   tip_h=cfg.tip_h, apex_field=cfg.apex_field, phi_w=cfg.phi_w, dt=cfg.dt, xi=cfg.xi,
+                   m_ion=cfg.m_ion, seed=cfg.seed, xs_n=len(keep[0]), solver=solver, xs_emin=cfg.xs_emin,
+                   xs_emax=cfg.xs_emax, xs_el=keep[0].ctypes.data_as(dp), xs_iz=keep[1].ctypes.data_as(dp),
+                   xs_cx=keep[2].ctypes.data_as(dp), fn_rings=cfg.fn_rings, fn_az=cfg.fn_az,
+                   laplace_rtol=laplace_rtol, step_rtol=step_rtol, step_maxit=step_maxit, sort_every=sort_every,
+                   id_capacity=id_capacity)
+    return c, keep
+
+
+class Simulation:
+    """One PIC-MCC instance on a GPU: torch tensors for every buffer of
+    pic_buffers, and the context."""
+
+    def __init__(self, cfg: workloads.Config, caps=(1 << 16, 1 << 14, 1 << 14), precision=PIC_F64,
+                 solver=PIC_SOLVER_CG, device="cuda", **kw):
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.dtype = torch.float32 if precision == PIC_F32 else torch.float64
+        self.precision = precision
+        self.c, self._keep = make_config(cfg, precision=precision, solver=solver, **kw)
+        self.caps = tuple(int(x) for x in caps)
+        nn = cfg.nx * cfg.ny * cfg.nz
+        dev = self.device
+        self.sp = []
+        for s in range(3):
+            cap = max(self.caps[s], 1)
+            arrs = {k: torch.zeros(cap, dtype=self.dtype, device=dev) for k in ("x", "y", "z", "vx", "vy", "vz")}
+            arrs["id"] = torch.full((cap,), -1, dtype=torch.int32, device=dev)
+            self.sp.append(arrs)
+        self.phi = torch.zeros(nn, dtype=torch.float64, device=dev)
+        self.phi1 = torch.zeros(nn, dtype=torch.float64, device=dev)
+        self.rho = torch.zeros(nn, dtype=torch.int64, device=dev)
+        self.field = torch.zeros(4 * nn, dtype=self.dtype, device=dev)
+        self.field0 = torch.zeros(4 * nn, dtype=self.dtype, device=dev)
+        self.node_type = torch.zeros(nn, dtype=torch.uint8, device=dev)
+        nbytes = pic_scratch_size(self.c, self.caps)
+        self._scratch_raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        base = self._scratch_raw.data_ptr()
+        self._scratch_off = (-base) % 256
+        b = pic_buffers()
+        for s in range(3):
+            for k in ("x", "y", "z", "vx", "vy", "vz"):
+                getattr(b, k)[s] = self.sp[s][k].data_ptr()
+            b.id[s] = self.sp[s]["id"].data_ptr()
+            b.cap[s] = self.caps[s]
+        b.phi, b.phi1, b.rho = self.phi.data_ptr(), self.phi1.data_ptr(), self.rho.data_ptr()
+        b.field, b.field0, b.node_type = self.field.data_ptr(), self.field0.data_ptr(), self.node_type.data_ptr()
+        b.scratch = base + self._scratch_off
+        b.scratch_bytes = nbytes
+        self.bufs = b
+        self.stream = torch.cuda.current_stream(dev)
+        torch.cuda.synchronize(dev)
+        self.ctx = pic_init(self.c, b, self.stream.cuda_stream)
+
+    def close(self):
+        if self.ctx is not None:
+            pic_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- convenience wrappers ------------------------------------------------
+    def load(self, load: dict):
+        """Append a particle load (dict species name -> x..vz arrays), in the
+        order electrons, ions, neutrals."""
+        for s, name in enumerate(workloads.SPECIES):
+            if name not in load:
+                continue
+            a = load[name]
+            n = len(a["x"])
+            if n == 0:
+                continue
+            t = {k: torch.as_tensor(np.asarray(a[k]), dtype=self.dtype).to(self.device) for k in
+                 ("x", "y", "z", "vx", "vy", "vz")}
+            src = pic_particles(species=s, n=n, **{k: v.data_ptr() for k, v in t.items()})
+            torch.cuda.synchronize(self.device)
+            pic_inject(self.ctx, src)
+
+    def inject(self) -> int:
+        return pic_inject(self.ctx, None)
+
+    def step(self, nsteps=1, flags=STEP_FULL) -> int:
+        return pic_step(self.ctx, nsteps, flags)
+
+    def solve(self, solver=PIC_SOLVER_CG, guess=PIC_GUESS_PREVIOUS, rtol=1e-8, maxit=100000, **kw) -> dict:
+        return pic_solve_poisson(self.ctx, solver, guess, rtol, maxit, **kw)
+
+    def moments(self) -> dict:
+        return pic_moments(self.ctx)
+
+    def events(self, cap=None) -> list:
+        if cap is None:
+            cap = self.caps[2] + 16
+        return pic_events(self.ctx, cap)
+
+    def set_phi(self, phi: np.ndarray):
+        self.phi.copy_(torch.as_tensor(np.asarray(phi, np.float64)).to(self.device))
+        torch.cuda.synchronize(self.device)
+        pic_step(self.ctx, 1, STEP_FIELD)
+
+    def state(self) -> list:
+        """Alive particles per species as numpy arrays (ids as uint32)."""
+        m = self.moments()
+        out = []
+        for s in range(3):
+            n = int(m["n_slots"][s])
+            d = {k: self.sp[s][k][:n].cpu().numpy().astype(np.float64) for k in ("x", "y", "z", "vx", "vy", "vz")}
+            ids = self.sp[s]["id"][:n].cpu().numpy().view(np.uint32)
+            alive = ids != DEAD
+            d = {k: v[alive] for k, v in d.items()}
+            d["id"] = ids[alive]
+            out.append(d)
+        return out
+
+    def grid(self, name: str) -> np.ndarray:
+        t = getattr(self, name)
+        torch.cuda.synchronize(self.device)
+        return t.cpu().numpy()

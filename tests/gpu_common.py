@@ -1,0 +1,97 @@
+"""Helpers of the GPU parity tests: build a GPU instance and an oracle
+instance from the same seeded inputs and compare them particle by particle."""
+import numpy as np
+
+import oracle
+from paper_2402_08404_amd import workloads as W
+
+
+def round_load(load, precision):
+    """The load as the GPU stores it (float32 in FP32 mode), in float64."""
+    if precision == 1:
+        return {s: {k: np.asarray(v, np.float32).astype(np.float64) for k, v in d.items()} for s, d in load.items()}
+    return load
+
+
+def by_id(st):
+    return {int(i): k for k, i in enumerate(st["id"])}
+
+
+def boundary_margin(cfg, X, Y, Z):
+    """Distance (grid units) of points from every surface where the removal
+    test changes its answer."""
+    R, H = cfg.tip_r / cfg.h, cfg.tip_h / cfg.h
+    xc, yc = (cfg.nx - 1) / 2, (cfg.ny - 1) / 2
+    zs = np.clip(Z, 0, H - R)
+    d_tip = np.abs(np.sqrt((X - xc) ** 2 + (Y - yc) ** 2 + (Z - zs) ** 2) - R)
+    return np.minimum.reduce([np.abs(Z), np.abs(Z - (cfg.nz - 1)), np.abs(X), np.abs(X - (cfg.nx - 1)),
+                              np.abs(Y), np.abs(Y - (cfg.ny - 1)), d_tip])
+
+
+def compare_states(cfg, gpu_st, orc_st, pos_tol, vel_tol, margin_tol=None):
+    """Compare alive particles by id. Particles present on one side only must
+    sit within margin_tol of a removal surface on the oracle side (or in its
+    pre-push state). Returns the number of compared particles."""
+    n = 0
+    for s in range(3):
+        g, o = gpu_st[s], orc_st[s]
+        gi, oi = by_id(g), by_id(o)
+        only_g = set(gi) - set(oi)
+        only_o = set(oi) - set(gi)
+        if margin_tol is None:
+            assert not only_g and not only_o, (s, sorted(only_g)[:5], sorted(only_o)[:5])
+        else:
+            for i in only_g:
+                k = gi[i]
+                m = boundary_margin(cfg, g["x"][k], g["y"][k], g["z"][k])
+                assert m < margin_tol, (s, i, m)
+            for i in only_o:
+                k = oi[i]
+                m = boundary_margin(cfg, o["x"][k], o["y"][k], o["z"][k])
+                assert m < margin_tol, (s, i, m)
+        common = sorted(set(gi) & set(oi))
+        if not common:
+            continue
+        a = np.array([gi[i] for i in common])
+        b = np.array([oi[i] for i in common])
+        for k in ("x", "y", "z"):
+            d = np.abs(g[k][a] - o[k][b])
+            assert (d <= pos_tol * np.maximum(1.0, np.abs(o[k][b]))).all(), (s, k, d.max())
+        vs = max(np.abs(np.concatenate([o["vx"][b], o["vy"][b], o["vz"][b]])).max(), 1e-300)
+        for k in ("vx", "vy", "vz"):
+            d = np.abs(g[k][a] - o[k][b])
+            assert (d <= vel_tol * (np.abs(o[k][b]) + 1e-3 * vs)).all(), (s, k, (d / (np.abs(o[k][b]) + 1e-3 * vs)).max())
+        n += len(common)
+    return n
+
+
+def event_sets(events, fragile):
+    """Events as a set of (kind, id_a, id_b), without the pairs whose decision
+    the oracle reports as fragile."""
+    out = set()
+    for kind, a, b, ni, ne in events:
+        if a in fragile or b in fragile:
+            continue
+        out.add((int(kind), int(a), int(b)))
+    return out
+
+
+def dense_load(cfg, ncell=300, per=(6, 1, 5), seed=3, speed_e=0.2, speed_i=0.002):
+    """Cells with several particles of every species (collision tests)."""
+    rng = np.random.default_rng(seed)
+    cells = rng.choice(cfg.n_cells, size=ncell, replace=False)
+    i = cells % (cfg.nx - 1)
+    j = (cells // (cfg.nx - 1)) % (cfg.ny - 1)
+    k = cells // ((cfg.nx - 1) * (cfg.ny - 1))
+    R, H = cfg.tip_r / cfg.h, cfg.tip_h / cfg.h
+    xc = (cfg.nx - 1) / 2
+    load = {}
+    for name, m, sp in zip(W.SPECIES, per, (speed_e, speed_i, speed_i * 0.5)):
+        X = np.repeat(i, m) + rng.uniform(0.02, 0.98, ncell * m)
+        Y = np.repeat(j, m) + rng.uniform(0.02, 0.98, ncell * m)
+        Z = np.repeat(k, m) + rng.uniform(0.02, 0.98, ncell * m)
+        zs = np.clip(Z, 0, H - R)
+        ok = (np.sqrt((X - xc) ** 2 + (Y - xc) ** 2 + (Z - zs) ** 2) > R + 0.05) & (Z > 0.05) & (Z < cfg.nz - 1.05)
+        v = rng.standard_normal((ncell * m, 3)) * sp
+        load[name] = {"x": X[ok], "y": Y[ok], "z": Z[ok], "vx": v[ok, 0], "vy": v[ok, 1], "vz": v[ok, 2]}
+    return load
