@@ -1,0 +1,232 @@
+#!/usr/bin/env python3
+"""Throughput of the PIC-MCC step on one MI355X.
+
+One step is the whole hot path: Fowler-Nordheim emission, gather + leapfrog
+push + boundary removal + fixed-point deposit + binning, Monte Carlo
+collisions (elastic, impact ionization, charge exchange), field ionization,
+products, and the Poisson solve to a relative residual of 1e-8 followed by the
+node field. The workload is the GPU-scale configuration: a 128 x 128 x 512
+node grid at 1 nm around a Cu tip (r = 10 nm, H = 100 nm, 10 GV/m at the
+apex) with 20 M particles stored as FP32 SoA (16 M electrons at kT = 5 eV,
+1 M Cu+ at 1 eV, 3 M Cu at 0.1 eV, uniform over the vacuum box), synthetic
+256-node cross-section tables, dt = 5e-17 s. Inputs are generated on the host,
+copied to the GPU and resident in HBM before timing starts.
+
+Prints one JSON line (see the README of the metric fields in the design doc).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s (push+deposit+MCC) + CG iters to 1e-8: learned vs plain"
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name):
+    import numpy as np
+    from paper_2402_08404_amd import workloads as W
+    if name == "gpu_scale":
+        cfg = W.gpu_scale()
+        counts = (16_000_000, 1_000_000, 3_000_000)
+        kT = (5.0, 1.0, 0.1)
+        region = "box"
+    elif name == "tiny":
+        cfg = W.tiny()
+        counts = (20000, 200, 2000)
+        kT = None
+        region = "near_tip"
+    else:
+        raise SystemExit("unknown workload " + name)
+    return cfg, counts, kT, region, np
+
+
+def push_bytes(n_particles, n_nodes, fp32=True):
+    """Algorithmic bytes of one push launch: per particle read x, v and the id,
+    write x, v, the cell key and the slot; per node one read of the field
+    (4 values) and one write of the int64 charge."""
+    t = 4 if fp32 else 8
+    per_p = 6 * t + 4 + 6 * t + 8
+    per_n = 4 * t + 8
+    return per_p * n_particles + per_n * n_nodes
+
+
+def cg_bytes(n_nodes):
+    """Algorithmic bytes of the two CG kernels of one iteration: (a) read r and
+    p, write p' and q = A p' (the 7-point stencil reuses neighbours from cache),
+    node type; (b) read x, p', r, q and the node type, write x and r."""
+    return 33 * n_nodes, 49 * n_nodes
+
+
+def cpu_baseline(cfg_name, sample, steps, np):
+    """The CPU oracle (single thread, FP64) on a bounded sample of the same
+    workload: `sample` particles with the same species mix and distributions
+    on the same grid, timed over `steps` steps of push, collisions and
+    deposit. The oracle's Poisson solve is left out (a solve of the
+    128 x 128 x 512 grid takes minutes on one core); a smooth synthetic
+    potential stands in for the field."""
+    import oracle
+    from paper_2402_08404_amd import workloads as W
+    cfg, counts, kT, region, _ = workload(cfg_name)
+    frac = sample / sum(counts)
+    sub = tuple(int(round(c * frac)) for c in counts)
+    o = oracle.Oracle(cfg, laplace=False)
+    o.load(W.initial_load(cfg, counts=sub, kT_eV=kT, region=region, seed=cfg.seed + 7))
+    o.set_phi(W.synthetic_potential(cfg, o.V0))
+    n = sum(s.n for s in o.sp)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        o.push()
+        o.collide()
+        o.deposit()
+        o.step_no += 1
+    dt = time.perf_counter() - t0
+    return {"value": n * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} particles ({sub[0]} e, {sub[1]} Cu+, {sub[2]} Cu) of the same workload, {steps} steps "
+                      f"of push+collisions+deposit on the same grid, synthetic potential, solve excluded; "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="gpu_scale", choices=["gpu_scale", "tiny"])
+    ap.add_argument("--solver", default="cg", choices=["cg", "mgcg", "mixed"])
+    ap.add_argument("--sort-every", type=int, default=16)
+    ap.add_argument("--cpu-sample", type=int, default=3_000_000)
+    ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--skip-zero-solve", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
+              "described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2402_08404_amd import pic
+    from paper_2402_08404_amd import workloads as W
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    cfg, counts, kT, region, np = workload(args.workload)
+    solver = {"cg": pic.PIC_SOLVER_CG, "mgcg": pic.PIC_SOLVER_MGCG, "mixed": pic.PIC_SOLVER_MIXED}[args.solver]
+    fp32 = args.workload == "gpu_scale"
+    caps = (counts[0] + counts[2] + max(counts[0] // 8, 4096), counts[1] + counts[2] + max(counts[1] // 8, 4096),
+            counts[2] + 1024)
+    t_setup = time.perf_counter()
+    sim = pic.Simulation(cfg, caps=caps, precision=pic.PIC_F32 if fp32 else pic.PIC_F64, solver=solver,
+                         step_rtol=1e-8, step_maxit=20000, sort_every=args.sort_every)
+    log(f"[bench] init done ({time.perf_counter() - t_setup:.1f} s), generating {sum(counts)} particles")
+    load = W.initial_load(cfg, counts=counts, kT_eV=kT, region=region,
+                          dtype=np.float32 if fp32 else np.float64)
+    sim.load(load)
+    del load
+    sim.step(1, pic.STEP_DEPOSIT)
+    nn = cfg.nx * cfg.ny * cfg.nz
+    # CG iterations to 1e-8 from a zero guess (plain CG) and from V0 phi1
+    cg_info = {}
+    if not args.skip_zero_solve:
+        saved = sim.phi.clone()
+        r0 = sim.solve(solver=pic.PIC_SOLVER_CG, guess=pic.PIC_GUESS_ZERO, rtol=1e-8, maxit=200000)
+        cg_info["plain_zero_guess_iters"] = r0["iterations"]
+        sim.phi.copy_(saved)
+    r1 = sim.solve(solver=solver, guess=pic.PIC_GUESS_PREVIOUS, rtol=1e-8, maxit=200000)
+    cg_info["initial_solve_iters"] = r1["iterations"]
+    log(f"[bench] setup {time.perf_counter() - t_setup:.1f} s; warmup {args.warmup} steps")
+    sim.step(args.warmup, pic.STEP_FULL)
+    m0 = sim.moments()
+    it0 = m0["cg_iters_total"]
+
+    pic.pic_profile(sim.ctx, True)
+    pic.pic_timers(sim.ctx, reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(args.steps, pic.STEP_FULL)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = pic.pic_timers(sim.ctx, reset=True)
+    pic.pic_profile(sim.ctx, False)
+    m1 = sim.moments()
+    log(f"[bench] timed {args.steps} steps in {wall:.3f} s")
+
+    n_avg = 0.5 * (m0["n_alive"].sum() + m1["n_alive"].sum())
+    ne_avg = 0.5 * (m0["n_alive"][0] + m1["n_alive"][0])
+    ms_step = 1e3 * wall / args.steps
+    value = n_avg * args.steps / wall
+
+    def avg(name):
+        ms, cnt = tm[name]
+        return ms / cnt if cnt else float("nan")
+
+    particle_ms = tm["inject"][0] + tm["particles"][0] + tm["collide"][0]
+    solve_ms = tm["solve"][0]
+    k_push_e = avg("push_e")
+    pb = push_bytes(ne_avg, nn, fp32)
+    ca, cb = cg_bytes(nn)
+    kernels = {
+        "push_electrons": {"avg_ms": k_push_e, "bytes": pb, "gbs": pb / (k_push_e * 1e-3) / 1e9},
+        "cg_a": {"avg_ms": avg("cg_a"), "bytes": ca, "gbs": ca / (avg("cg_a") * 1e-3) / 1e9},
+        "cg_b": {"avg_ms": avg("cg_b"), "bytes": cb, "gbs": cb / (avg("cg_b") * 1e-3) / 1e9},
+    }
+    # dominant kernel of the timed steps: the electron push, or the CG pair
+    push_total = tm["push_e"][0]
+    cg_total_est = solve_ms
+    if push_total >= cg_total_est or not tm["cg_a"][1]:
+        dom, k = "push_electrons", kernels["push_electrons"]
+    else:
+        dom = "cg_a" if kernels["cg_a"]["avg_ms"] * tm["cg_a"][1] >= kernels["cg_b"]["avg_ms"] * tm["cg_b"][1] \
+            else "cg_b"
+        k = kernels[dom]
+    roof = {"kernel": dom, "bound": "hbm", "achieved": round(k["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(k["gbs"] / HBM_PEAK_GBS, 4), "traffic": None}
+
+    out = {
+        "metric": METRIC,
+        "value": float(value),
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if fp32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "grid": [cfg.nx, cfg.ny, cfg.nz], "h_m": cfg.h,
+                   "particles": list(counts), "particle_state": "fp32" if fp32 else "fp64",
+                   "poisson": f"{args.solver} fp64 rtol 1e-8, previous-step guess", "sort_every": args.sort_every},
+        "roofline": roof,
+        "breakdown_ms_per_step": {k2: tm[k2][0] / args.steps for k2 in
+                                  ("inject", "particles", "push", "collide", "mcc", "solve", "step")},
+        "particle_phases": {"value": float(n_avg * args.steps / (particle_ms * 1e-3)) if particle_ms else None,
+                            "unit": "particle-steps/s", "what": "emission + push/deposit/binning + collisions, "
+                                                                "HIP-event time on the library stream"},
+        "kernels": kernels,
+        "cg": dict(cg_info, step_iters_avg=(m1["cg_iters_total"] - it0) / args.steps, learned=None),
+        "alive": [int(x) for x in m1["n_alive"]],
+        "events_total": [int(x) for x in m1["events"]],
+    }
+    if tm["cg_a"][1]:
+        out["cg"]["step_solve_ms_avg"] = solve_ms / args.steps
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample, args.cpu_steps, np)
+    else:
+        out["cpu_baseline"] = None
+    sim.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

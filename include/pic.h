@@ -162,7 +162,9 @@ typedef struct pic_moments_t {
     double v0;                 /* anode potential [V] */
     double apex_field1;        /* Laplace apex field per volt of anode potential [1/m] */
     int32_t error;             /* sticky error code, PIC_OK if none */
-    int32_t pad;
+    int32_t last_cg_iters;     /* iterations of the last Poisson solve */
+    double last_cg_relres;     /* final relative residual of the last solve */
+    int64_t cg_iters_total;    /* iterations of all solves since pic_init (the init solve excluded) */
 } pic_moments_t;
 
 typedef struct pic_event {
@@ -209,6 +211,27 @@ pic_status pic_moments(pic_ctx* ctx, pic_moments_t* out);
 /* Copy up to cap events of the last collide phase run with PIC_STEP_EVENTS;
  * n receives the number recorded. */
 pic_status pic_events(pic_ctx* ctx, pic_event* out, int64_t cap, int64_t* n);
+
+/* Timers. With profiling enabled, pic_step and pic_solve_poisson record HIP
+ * events on the context stream around each phase and around the hot kernels;
+ * pic_timers adds up the elapsed times since the last reset (synchronizes). */
+#define PIC_T_INJECT 0        /* emission phase */
+#define PIC_T_PUSH_E 1        /* electron push kernel (gather, push, deposit, binning) */
+#define PIC_T_PUSH 2          /* the three push kernels */
+#define PIC_T_PARTICLES 3     /* push phase: clearing of rho and counters, push kernels */
+#define PIC_T_COLLIDE 4       /* collide phase: bins, MCC, field ionization, products, reordering */
+#define PIC_T_MCC 5           /* the two MCC kernels */
+#define PIC_T_SOLVE 6         /* Poisson solve and node field */
+#define PIC_T_CG_A 7          /* CG kernel: p update, matrix product, p.q */
+#define PIC_T_CG_B 8          /* CG kernel: x and r update, r.r */
+#define PIC_T_STEP 9          /* whole steps of pic_step */
+#define PIC_T_MG 10           /* multigrid V-cycles */
+#define PIC_NTIMERS 12
+
+pic_status pic_profile(pic_ctx* ctx, int32_t enable);
+/* ms[PIC_NTIMERS]: summed milliseconds; count[PIC_NTIMERS]: number of timed
+ * intervals; reset != 0 clears the sums afterwards. */
+pic_status pic_timers(pic_ctx* ctx, double* ms, int64_t* count, int32_t reset);
 
 const char* pic_last_error(const pic_ctx* ctx);
 void pic_destroy(pic_ctx* ctx);

@@ -193,7 +193,10 @@ class _SpeciesStore:
 class Oracle:
     """The whole PIC-MCC state of one instance, advanced step by step."""
 
-    def __init__(self, cfg, laplace_rtol: float = 1e-13):
+    def __init__(self, cfg, laplace_rtol: float = 1e-13, laplace: bool = True):
+        """laplace=False skips the unit-anode Laplace solve and uses the
+        plain linear ramp between the plates in its place (only for timing
+        the particle stages on grids too large to solve on one core)."""
         self.cfg = cfg
         self.c, self._keep = make_config(cfg)
         self.L = lib()
@@ -204,8 +207,12 @@ class Oracle:
         # requested apex field, and the Shockley-Ramo weighting field.
         self.phi1 = np.zeros(N)
         rr = C.c_double()
-        self.laplace_iters = self.L.orc_solve(C.byref(self.c), self.type, np.zeros(N, np.int64), 1.0,
-                                              self.phi1, laplace_rtol, 100000, C.byref(rr))
+        if laplace:
+            self.laplace_iters = self.L.orc_solve(C.byref(self.c), self.type, np.zeros(N, np.int64), 1.0,
+                                                  self.phi1, laplace_rtol, 100000, C.byref(rr))
+        else:
+            self.laplace_iters = 0
+            self.phi1 = np.repeat(np.arange(cfg.nz) / (cfg.nz - 1), cfg.nx * cfg.ny).astype(np.float64)
         self.F1 = self.L.orc_apex_field(C.byref(self.c), self.phi1)
         self.V0 = cfg.apex_field / self.F1
         self.E0 = np.zeros(3 * N)

@@ -208,11 +208,16 @@ hipError_t scan_u32(pic_ctx* c, const uint32_t* in, uint32_t* out, int64_t n_max
 }
 
 // ---------------------------------------------------------------------------
-// Conjugate gradients. Two fused kernels per iteration; the scalars live on
-// the device and each reduction is finished by the last block to arrive,
-// summing the block partials in index order (deterministic). Kernels return
-// at once when the solve is done, so the host can enqueue iterations in
-// chunks and test convergence once per chunk.
+// Conjugate gradients. Two kernels per iteration over a fixed grid of
+// kCgBlocks blocks, each block owning a contiguous chunk of nodes (chunks of
+// one XCD are adjacent, so stencil neighbours stay in that XCD's L2). A
+// reduction is finished by the next kernel: every block sums the previous
+// kernel's per-block partials in the same fixed order (deterministic, and no
+// device-wide fence, which on this GPU would write back the whole L2). The
+// scalars live on the device; kernels return at once when the solve is done,
+// so the host enqueues iterations in chunks and tests convergence per chunk.
+
+constexpr int kCgBlocks = 1024;
 
 struct CgArgs {
     Grid g;
@@ -226,35 +231,13 @@ struct CgArgs {
     double qscale;   // 2^-40 e / (eps0 h)
     double V0;
     DevState* s;
-    double* partials;
+    double* part_pq;  // kCgBlocks partials of p.q
+    double* part_rr;  // kCgBlocks partials of r.r
+    double* part_bb;  // kCgBlocks partials of b.b
+    int64_t chunk;    // nodes per block (multiple of the block size)
 };
 
 __device__ inline double half_at_edge(int i, int n) { return (i == 0 || i == n - 1) ? 0.5 : 1.0; }
-
-// Last-block reduction of per-block partials; returns true in the one thread
-// that holds the total in *tot.
-__device__ inline bool finish_sum(double v, double* partials, unsigned int* counter, double* tot) {
-    __shared__ double sh[kBlock / 64];
-    __shared__ int last;
-    double b = block_sum(v, sh);
-    if (threadIdx.x == 0) {
-        partials[blockIdx.x] = b;
-        __threadfence();
-        unsigned int prev = atomicAdd(counter, 1u);
-        last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < gridDim.x; i += blockDim.x) s += ((volatile double*)partials)[i];
-    double t = block_sum(s, sh);  // fixed order: strided per thread, then tree
-    if (threadIdx.x == 0) {
-        *counter = 0u;
-        *tot = t;
-    }
-    return threadIdx.x == 0;
-}
 
 __device__ inline void node_ijk(const Grid& g, int64_t n, int& i, int& j, int& k) {
     i = (int)(n % g.nx);
@@ -262,7 +245,26 @@ __device__ inline void node_ijk(const Grid& g, int64_t n, int& i, int& j, int& k
     k = (int)(n / ((int64_t)g.nx * g.ny));
 }
 
-// Dirichlet values into phi, optional zero guess, p_new cleared.
+// Sum of kCgBlocks partials in a fixed order; the result is returned to every
+// thread of the block.
+__device__ inline double sum_partials(const double* part) {
+    __shared__ double sh[kBlock / 64];
+    __shared__ double res;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < kCgBlocks; i += blockDim.x) v += part[i];
+    double t = block_sum(v, sh);
+    if (threadIdx.x == 0) res = t;
+    __syncthreads();
+    return res;
+}
+
+__device__ inline void write_partial(double v, double* part) {
+    __shared__ double sh[kBlock / 64];
+    double t = block_sum(v, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// Dirichlet values into phi, optional zero guess.
 __global__ void k_cg_init(CgArgs a, int zero_guess) {
     const Grid& g = a.g;
     int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -274,25 +276,27 @@ __global__ void k_cg_init(CgArgs a, int zero_guess) {
     } else if (zero_guess) {
         a.x[n] = 0.0;
     }
-    a.p_new[n] = 0.0;
 }
 
-// r = q/(eps0 h) - L(phi) with the Dirichlet values in phi, and the norms of
-// r and of b = q/(eps0 h) + Dirichlet lifts.
-__global__ void k_cg_resid(CgArgs a) {
+// r = q/(eps0 h) - L(phi) with the Dirichlet values in phi, partials of r.r
+// and of b.b with b = q/(eps0 h) + Dirichlet lifts; p_old cleared.
+__global__ __launch_bounds__(kBlock) void k_cg_resid(CgArgs a) {
     const Grid& g = a.g;
-    int64_t n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    int64_t b0 = xcd_block(blockIdx.x, gridDim.x) * a.chunk;
+    int64_t b1 = b0 + a.chunk < g.nn ? b0 + a.chunk : g.nn;
+    int64_t pl = (int64_t)g.nx * g.ny;
     double bb = 0.0, rr = 0.0;
-    if (n < g.nn && a.type[n] == 0) {
+    for (int64_t n = b0 + threadIdx.x; n < b1; n += blockDim.x) {
+        ((double*)a.p_old)[n] = 0.0;
+        if (a.type[n] != 0) continue;
         int i, j, k;
         node_ijk(g, n, i, j, k);
-        int64_t pl = (int64_t)g.nx * g.ny;
         double fx = half_at_edge(j, g.ny) * half_at_edge(k, g.nz);
         double fy = half_at_edge(i, g.nx) * half_at_edge(k, g.nz);
         double fz = half_at_edge(i, g.nx) * half_at_edge(j, g.ny);
         double xi = a.x[n];
         double qv = (double)a.rho[n] * a.qscale;
-        double b = qv, lx = 0.0;
+        double bv = qv, lx = 0.0;
         int64_t nb[6] = {n - 1, n + 1, n - g.nx, n + g.nx, n - pl, n + pl};
         bool has[6] = {i > 0, i < g.nx - 1, j > 0, j < g.ny - 1, true, true};
         double f[6] = {fx, fx, fy, fy, fz, fz};
@@ -301,113 +305,101 @@ __global__ void k_cg_resid(CgArgs a) {
             if (!has[d]) continue;
             double xj = a.x[nb[d]];
             lx += f[d] * (xi - xj);
-            if (a.type[nb[d]] != 0) b += f[d] * xj;
+            if (a.type[nb[d]] != 0) bv += f[d] * xj;
         }
-        double r = qv - lx;
-        a.r[n] = r;
-        bb = b * b;
-        rr = r * r;
+        double rv = qv - lx;
+        a.r[n] = rv;
+        bb += bv * bv;
+        rr += rv * rv;
     }
-    // two reductions: b.b then r.r, both finished by the last block
-    __shared__ double sh[kBlock / 64];
-    __shared__ int last;
-    double sb = block_sum(bb, sh);
-    double sr = block_sum(rr, sh);
-    if (threadIdx.x == 0) {
-        a.partials[2 * blockIdx.x] = sb;
-        a.partials[2 * blockIdx.x + 1] = sr;
-        __threadfence();
-        unsigned int prev = atomicAdd(&a.s->red_count, 1u);
-        last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    double tb = 0.0, tr = 0.0;
-    for (int64_t q = threadIdx.x; q < gridDim.x; q += blockDim.x) {
-        tb += ((volatile double*)a.partials)[2 * q];
-        tr += ((volatile double*)a.partials)[2 * q + 1];
-    }
-    tb = block_sum(tb, sh);
-    tr = block_sum(tr, sh);
-    if (threadIdx.x == 0) {
-        DevState* s = a.s;
-        s->red_count = 0u;
-        s->bb = tb;
-        s->rr = tr;
-        s->rr0 = tr;
-        s->beta = 0.0;
-        s->it = 0;
-        s->zero_solution = (tb == 0.0);
-        s->done = (tb == 0.0) || (sqrt(tr) <= s->rtol * sqrt(tb)) || (s->maxit <= 0);
-    }
+    write_partial(bb, a.part_bb);
+    write_partial(rr, a.part_rr);
 }
 
-// p_new = r + beta p_old, q = A p_new, partial p_new . q; alpha = rr / pq.
-__global__ void k_cg_a(CgArgs a) {
+// Iteration it: finish r.r of the previous iteration (or of the initial
+// residual), test convergence, then p_new = r + beta p_old, q = A p_new and
+// the partials of p_new . q.
+__global__ __launch_bounds__(kBlock) void k_cg_a(CgArgs a, int it) {
     DevState* s = a.s;
     if (s->done) return;
     const Grid& g = a.g;
-    double beta = s->beta;
-    int64_t n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    double rr = sum_partials(a.part_rr);
+    double bb;
+    if (it == 0) {
+        bb = sum_partials(a.part_bb);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            s->bb = bb;
+            s->rr0 = rr;
+        }
+    } else {
+        bb = s->bb;
+    }
+    bool conv = (bb == 0.0) || (sqrt(rr) <= s->rtol * sqrt(bb)) || (it >= s->maxit);
+    double beta = it == 0 ? 0.0 : rr / s->rrbuf[(it - 1) & 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s->rrbuf[it & 1] = rr;
+        s->rr = rr;
+        s->it = it;
+        if (conv) {
+            s->done = 1;
+            s->zero_solution = (bb == 0.0);
+        }
+    }
+    if (conv) return;
+    int64_t b0 = xcd_block(blockIdx.x, gridDim.x) * a.chunk;
+    int64_t b1 = b0 + a.chunk < g.nn ? b0 + a.chunk : g.nn;
+    int64_t pl = (int64_t)g.nx * g.ny;
     double pq = 0.0;
-    if (n < g.nn) {
+    for (int64_t n = b0 + threadIdx.x; n < b1; n += blockDim.x) {
         if (a.type[n] != 0) {
             a.p_new[n] = 0.0;
             a.q[n] = 0.0;
-        } else {
-            int i, j, k;
-            node_ijk(g, n, i, j, k);
-            int64_t pl = (int64_t)g.nx * g.ny;
-            double fx = half_at_edge(j, g.ny) * half_at_edge(k, g.nz);
-            double fy = half_at_edge(i, g.nx) * half_at_edge(k, g.nz);
-            double fz = half_at_edge(i, g.nx) * half_at_edge(j, g.ny);
-            double pi = a.r[n] + beta * a.p_old[n];
-            double acc = 0.0;
-            int64_t nb[6] = {n - 1, n + 1, n - g.nx, n + g.nx, n - pl, n + pl};
-            bool has[6] = {i > 0, i < g.nx - 1, j > 0, j < g.ny - 1, true, true};
-            double f[6] = {fx, fx, fy, fy, fz, fz};
-#pragma unroll
-            for (int d = 0; d < 6; ++d) {
-                if (!has[d]) continue;
-                int64_t m = nb[d];
-                double pj = (a.type[m] == 0) ? a.r[m] + beta * a.p_old[m] : 0.0;
-                acc += f[d] * (pi - pj);
-            }
-            a.p_new[n] = pi;
-            a.q[n] = acc;
-            pq = pi * acc;
+            continue;
         }
+        int i, j, k;
+        node_ijk(g, n, i, j, k);
+        double fx = half_at_edge(j, g.ny) * half_at_edge(k, g.nz);
+        double fy = half_at_edge(i, g.nx) * half_at_edge(k, g.nz);
+        double fz = half_at_edge(i, g.nx) * half_at_edge(j, g.ny);
+        double pi = a.r[n] + beta * a.p_old[n];
+        double acc = 0.0;
+        int64_t nb[6] = {n - 1, n + 1, n - g.nx, n + g.nx, n - pl, n + pl};
+        bool has[6] = {i > 0, i < g.nx - 1, j > 0, j < g.ny - 1, true, true};
+        double f[6] = {fx, fx, fy, fy, fz, fz};
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            if (!has[d]) continue;
+            int64_t m = nb[d];
+            double pj = (a.type[m] == 0) ? a.r[m] + beta * a.p_old[m] : 0.0;
+            acc += f[d] * (pi - pj);
+        }
+        a.p_new[n] = pi;
+        a.q[n] = acc;
+        pq += pi * acc;
     }
-    double tot;
-    if (finish_sum(pq, a.partials, &s->red_count, &tot)) {
-        s->pq = tot;
-        s->alpha = s->rr / tot;
-    }
+    write_partial(pq, a.part_pq);
 }
 
-// x += alpha p, r -= alpha q, partial r.r; beta, convergence test.
-__global__ void k_cg_b(CgArgs a) {
+// Iteration it: alpha = rr / pq, x += alpha p, r -= alpha q, partials of r.r.
+__global__ __launch_bounds__(kBlock) void k_cg_b(CgArgs a, int it) {
     DevState* s = a.s;
     if (s->done) return;
     const Grid& g = a.g;
-    double alpha = s->alpha;
-    int64_t n = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+    double pq = sum_partials(a.part_pq);
+    double alpha = s->rrbuf[it & 1] / pq;
+    int64_t b0 = xcd_block(blockIdx.x, gridDim.x) * a.chunk;
+    int64_t b1 = b0 + a.chunk < g.nn ? b0 + a.chunk : g.nn;
     double rr = 0.0;
-    if (n < g.nn && a.type[n] == 0) {
+    for (int64_t n = b0 + threadIdx.x; n < b1; n += blockDim.x) {
+        if (a.type[n] != 0) continue;
         double p = a.p_new[n];
         a.x[n] += alpha * p;
         double r = a.r[n] - alpha * a.q[n];
         a.r[n] = r;
-        rr = r * r;
+        rr += r * r;
     }
-    double tot;
-    if (finish_sum(rr, a.partials, &s->red_count, &tot)) {
-        s->beta = tot / s->rr;
-        s->rr = tot;
-        s->it += 1;
-        s->done = (sqrt(tot) <= s->rtol * sqrt(s->bb)) || (s->it >= s->maxit);
-    }
+    write_partial(rr, a.part_rr);
+    if (blockIdx.x == 0 && threadIdx.x == 0) s->it = it + 1;
 }
 
 __global__ void k_cg_zero_free(Grid g, const uint8_t* type, double* x, const DevState* s) {
@@ -420,7 +412,8 @@ __global__ void k_cg_setup(DevState* s, double rtol, int maxit) {
     s->rtol = rtol;
     s->maxit = maxit;
     s->done = 0;
-    s->red_count = 0u;
+    s->it = 0;
+    s->zero_solution = 0;
 }
 
 int cg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess, double rtol, int maxit,
@@ -439,30 +432,36 @@ int cg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess, 
     a.qscale = ldexp(1.0, -40) * kQe / (kEps0 * g.h);
     a.V0 = V0;
     a.s = c->st;
-    a.partials = c->partials;
+    a.part_pq = c->partials;
+    a.part_rr = c->partials + kCgBlocks;
+    a.part_bb = c->partials + 2 * kCgBlocks;
+    a.chunk = ((g.nn + kCgBlocks - 1) / kCgBlocks + kBlock - 1) / kBlock * kBlock;
     hipLaunchKernelGGL(k_cg_setup, dim3(1), dim3(1), 0, c->stream, c->st, rtol, maxit);
     hipLaunchKernelGGL(k_cg_init, dim3((unsigned)G), dim3(kBlock), 0, c->stream, a, guess == PIC_GUESS_ZERO);
-    // p_old must read as zero in the first iteration (beta = 0 and p_old = r
-    // would also do; zero is cleaner)
-    (void)launch_zero(c->cg_p0, sizeof(double) * g.nn, c->stream);
-    hipLaunchKernelGGL(k_cg_resid, dim3((unsigned)G), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(k_cg_resid, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a);
     double* pa = c->cg_p0;
     double* pb = c->cg_p1;
     int chunk = 8;
     int launched = 0;
     while (true) {
-        for (int t = 0; t < chunk && launched < maxit; ++t, ++launched) {
+        for (int t = 0; t < chunk && launched <= maxit; ++t, ++launched) {
             a.p_old = pa;
             a.p_new = pb;
-            hipLaunchKernelGGL(k_cg_a, dim3((unsigned)G), dim3(kBlock), 0, c->stream, a);
-            hipLaunchKernelGGL(k_cg_b, dim3((unsigned)G), dim3(kBlock), 0, c->stream, a);
+            bool timed = launched < 256;  // per-kernel timing of the first iterations only
+            int ta = timed ? tic(c, PIC_T_CG_A) : -1;
+            hipLaunchKernelGGL(k_cg_a, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a, launched);
+            toc(c, ta);
+            if (launched == maxit) continue;  // the last launch only finishes r.r and the test
+            int tb = timed ? tic(c, PIC_T_CG_B) : -1;
+            hipLaunchKernelGGL(k_cg_b, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a, launched);
+            toc(c, tb);
             double* t2 = pa;
             pa = pb;
             pb = t2;
         }
         (void)hipMemcpyAsync(c->host_st, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream);
         if (hipStreamSynchronize(c->stream) != hipSuccess) return -2;
-        if (c->host_st->done || launched >= maxit) break;
+        if (c->host_st->done || launched > maxit) break;
         if (chunk < 64) chunk *= 2;
     }
     hipLaunchKernelGGL(k_cg_zero_free, dim3((unsigned)G), dim3(kBlock), 0, c->stream, g, c->buf.node_type, phi,

@@ -818,6 +818,8 @@ static hipError_t particles_t(pic_ctx* c, bool move) {
         a.x32 = pow(cf.xi, 1.5);
         a.dt_fs = cf.dt * 1e15;
         unsigned G = grid_for(a.s.cap);
+        int t_all = s == 0 ? tic(c, PIC_T_PUSH) : -1;
+        int t_e = s == 0 ? tic(c, PIC_T_PUSH_E) : -1;
         if (move) {
             if (s == 0) hipLaunchKernelGGL((k_push<T, 0, true>), dim3(G), dim3(kBlock), 0, c->stream, a);
             if (s == 1) hipLaunchKernelGGL((k_push<T, 1, true>), dim3(G), dim3(kBlock), 0, c->stream, a);
@@ -827,6 +829,9 @@ static hipError_t particles_t(pic_ctx* c, bool move) {
             if (s == 1) hipLaunchKernelGGL((k_push<T, 1, false>), dim3(G), dim3(kBlock), 0, c->stream, a);
             if (s == 2) hipLaunchKernelGGL((k_push<T, 2, false>), dim3(G), dim3(kBlock), 0, c->stream, a);
         }
+        toc(c, t_e);
+        if (s == 2) toc(c, c->push_all_handle);
+        if (s == 0) c->push_all_handle = t_all;
     }
     c->bins_dirty = 1;
     c->bins_valid = 1;
@@ -848,7 +853,8 @@ static hipError_t collide_t(pic_ctx* c, bool record) {
     for (int s = 0; s < 3; ++s)
         hipLaunchKernelGGL(k_scatter, dim3(grid_for(c->buf.cap[s])), dim3(kBlock), 0, c->stream, s, c->key[s],
                            c->slot[s], c->off, c->bins, c->st);
-    bool resort = cf.sort_every > 0 && ((c->collide_count + 1) % cf.sort_every) == 0;
+    bool resort = cf.sort_every > 0 && (c->need_sort || ((c->collide_count + 1) % cf.sort_every) == 0);
+    c->need_sort = 0;
     MccArgs<T> a;
     for (int s = 0; s < 3; ++s) a.sp[s] = species<T>(c, s);
     a.off = c->off;
@@ -877,8 +883,10 @@ static hipError_t collide_t(pic_ctx* c, bool record) {
     a.ev_cap = c->ev_cap;
     a.record = record ? 1 : 0;
     a.write_sorted = resort ? 1 : 0;
+    int tm = tic(c, PIC_T_MCC);
     hipLaunchKernelGGL(k_mcc_small<T>, dim3(grid_for(g.nc)), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(k_mcc_big<T>, dim3(1024), dim3(64), 0, c->stream, a);
+    toc(c, tm);
     hipLaunchKernelGGL(k_fi_resolve<T>, dim3(grid_for(c->buf.cap[2])), dim3(kBlock), 0, c->stream, a, c->fi_list,
                        c->bitmap[1]);
     // products

@@ -312,6 +312,7 @@ pic_status pic_inject(pic_ctx* c, const pic_particles* src, int64_t* n_added) {
         s = sync_state(c);
         if (s == PIC_OK && n_added) *n_added = src->n;
         c->bins_valid = 0;
+        c->need_sort = 1;  // order the load by cell at the next collide phase
         return s;
     }
     unsigned long long before = c->host_st->injected;
@@ -326,6 +327,7 @@ pic_status pic_inject(pic_ctx* c, const pic_particles* src, int64_t* n_added) {
 static pic_status solve(pic_ctx* c, int solver, int guess, double rtol, int maxit, pic_solve_info* info) {
     pic_solve_info tmp{};
     if (!info) info = &tmp;
+    int th = tic(c, PIC_T_SOLVE);
     int r;
     if (solver == PIC_SOLVER_CG)
         r = cg_solve(c, c->buf.phi, c->V0, c->buf.rho, guess, rtol, maxit, info);
@@ -336,7 +338,9 @@ static pic_status solve(pic_ctx* c, int solver, int guess, double rtol, int maxi
     if (r == -3) return fail(c, PIC_E_INVALID_ARG, "solver not available for this configuration");
     if (r != 0) return fail(c, PIC_E_HIP, "solver failed");
     c->last_solve = *info;
+    c->cg_iters_total += info->iterations;
     pic_status s = hip_check(c, launch_field(c, c->buf.phi, c->buf.field), "field");
+    toc(c, th);
     if (s != PIC_OK) return s;
     if (!info->converged) return fail(c, PIC_E_NOT_CONVERGED, "Poisson solve did not converge");
     return PIC_OK;
@@ -349,12 +353,23 @@ pic_status pic_step(pic_ctx* c, int32_t nsteps, uint32_t flags) {
     pic_status result = PIC_OK;
     for (int32_t n = 0; n < nsteps; ++n) {
         pic_status s = PIC_OK;
-        if (flags & PIC_STEP_INJECT) s = hip_check(c, inject_phase(c), "inject");
-        if (s == PIC_OK && (flags & (PIC_STEP_PUSH | PIC_STEP_DEPOSIT)))
+        if (c->prof && c->ev_n > c->ev_max / 4) flush_timers(c);
+        int th = tic(c, PIC_T_STEP);
+        if (flags & PIC_STEP_INJECT) {
+            int t = tic(c, PIC_T_INJECT);
+            s = hip_check(c, inject_phase(c), "inject");
+            toc(c, t);
+        }
+        if (s == PIC_OK && (flags & (PIC_STEP_PUSH | PIC_STEP_DEPOSIT))) {
+            int t = tic(c, PIC_T_PARTICLES);
             s = hip_check(c, particles_phase(c, (flags & PIC_STEP_PUSH) != 0), "push");
+            toc(c, t);
+        }
         if (s == PIC_OK && (flags & PIC_STEP_COLLIDE)) {
             if (!c->bins_valid) return fail(c, PIC_E_INVALID_ARG, "the collide phase needs a push or deposit phase first");
+            int t = tic(c, PIC_T_COLLIDE);
             s = hip_check(c, collide_phase(c, (flags & PIC_STEP_EVENTS) != 0), "collide");
+            toc(c, t);
         }
         if (s == PIC_OK && (flags & PIC_STEP_SOLVE)) {
             s = solve(c, c->cfg.solver, PIC_GUESS_PREVIOUS, c->cfg.step_rtol, c->cfg.step_maxit, nullptr);
@@ -365,6 +380,7 @@ pic_status pic_step(pic_ctx* c, int32_t nsteps, uint32_t flags) {
         } else if (s == PIC_OK && (flags & PIC_STEP_FIELD)) {
             s = hip_check(c, launch_field(c, c->buf.phi, c->buf.field), "field");
         }
+        toc(c, th);
         if (s != PIC_OK) return s;
         if (flags & PIC_STEP_ADVANCE) c->step++;
     }
@@ -378,6 +394,7 @@ pic_status pic_solve_poisson(pic_ctx* c, int32_t solver, int32_t guess, double r
     if (solver < PIC_SOLVER_CG || solver > PIC_SOLVER_MIXED || (guess != PIC_GUESS_ZERO && guess != PIC_GUESS_PREVIOUS) ||
         !(rtol > 0) || maxit < 0)
         return fail(c, PIC_E_INVALID_ARG, "bad solver arguments");
+    if (c->prof && c->ev_n > c->ev_max / 4) flush_timers(c);
     return solve(c, solver, guess, rtol, maxit, info);
 }
 
@@ -412,6 +429,9 @@ pic_status pic_moments(pic_ctx* c, pic_moments_t* out) {
     out->v0 = c->V0;
     out->apex_field1 = c->F1;
     out->error = h->error;
+    out->last_cg_iters = c->last_solve.iterations;
+    out->last_cg_relres = c->last_solve.relres;
+    out->cg_iters_total = c->cg_iters_total;
     return s;
 }
 
@@ -438,8 +458,82 @@ const char* pic_last_error(const pic_ctx* c) {
 void pic_destroy(pic_ctx* c) {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    if (c->evpool) {
+        for (int i = 0; i < c->ev_max; ++i) (void)hipEventDestroy(c->evpool[i]);
+        delete[] c->evpool;
+        delete[] c->ev_slot;
+    }
     if (c->host_st) (void)hipHostFree(c->host_st);
     delete c;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Profiling timers
+
+namespace pic {
+
+void flush_timers(pic_ctx* c) {
+    if (!c->evpool || c->ev_n == 0) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (int i = 0; i + 1 < c->ev_n; i += 2) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->evpool[i], c->evpool[i + 1]) == hipSuccess) {
+            int s = c->ev_slot[i / 2];
+            c->t_ms[s] += ms;
+            c->t_cnt[s] += 1;
+        }
+    }
+    c->ev_n = 0;
+}
+
+// Handles stay valid until the next flush, which happens only at the start of
+// an entry point (no interval is open then); a full pool skips timing.
+int tic(pic_ctx* c, int slot) {
+    if (!c->prof || c->ev_n + 2 > c->ev_max) return -1;
+    int h = c->ev_n;
+    c->ev_n += 2;
+    c->ev_slot[h / 2] = slot;
+    (void)hipEventRecord(c->evpool[h], c->stream);
+    return h;
+}
+
+void toc(pic_ctx* c, int h) {
+    if (h < 0 || !c->prof) return;
+    (void)hipEventRecord(c->evpool[h + 1], c->stream);
+}
+
+}  // namespace pic
+
+extern "C" {
+
+pic_status pic_profile(pic_ctx* c, int32_t enable) {
+    if (!c) return PIC_E_INVALID_ARG;
+    if (enable && !c->evpool) {
+        c->ev_max = 16384;
+        c->evpool = new hipEvent_t[c->ev_max];
+        c->ev_slot = new int[c->ev_max / 2];
+        for (int i = 0; i < c->ev_max; ++i)
+            if (hipEventCreate(&c->evpool[i]) != hipSuccess) return PIC_E_HIP;
+    }
+    if (!enable) flush_timers(c);
+    c->prof = enable ? 1 : 0;
+    return PIC_OK;
+}
+
+pic_status pic_timers(pic_ctx* c, double* ms, int64_t* count, int32_t reset) {
+    if (!c) return PIC_E_INVALID_ARG;
+    flush_timers(c);
+    for (int i = 0; i < PIC_NTIMERS; ++i) {
+        if (ms) ms[i] = c->t_ms[i];
+        if (count) count[i] = c->t_cnt[i];
+        if (reset) {
+            c->t_ms[i] = 0.0;
+            c->t_cnt[i] = 0;
+        }
+    }
+    return PIC_OK;
 }
 
 }  // extern "C"

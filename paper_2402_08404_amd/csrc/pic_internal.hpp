@@ -44,6 +44,7 @@ struct DevState {
     int error;
     // CG scalars
     double rr, bb, rr0, pq, alpha, beta, rtol;
+    double rrbuf[2];
     int it, maxit, done, zero_solution;
     unsigned int red_count;
     // mixed-precision refinement
@@ -220,11 +221,20 @@ struct pic_ctx {
     // host state
     pic::DevState* host_st = nullptr;  // pinned mirror
     int64_t step = 0;
-    int bins_valid = 0, bins_dirty = 0;
+    int bins_valid = 0, bins_dirty = 0, need_sort = 0;
     int64_t collide_count = 0;
     int failed = 0;
     std::string err;
     pic_solve_info last_solve{};
+    int64_t cg_iters_total = 0;
+    // profiling: pairs of events per timed interval
+    int prof = 0;
+    int push_all_handle = -1;
+    hipEvent_t* evpool = nullptr;
+    int ev_n = 0, ev_max = 0;
+    int* ev_slot = nullptr;
+    double t_ms[PIC_NTIMERS] = {};
+    int64_t t_cnt[PIC_NTIMERS] = {};
 };
 
 namespace pic {
@@ -248,4 +258,8 @@ hipError_t inject_phase(pic_ctx* c);
 hipError_t load_particles(pic_ctx* c, const pic_particles* src);
 hipError_t moments_phase(pic_ctx* c, double* out_dev);
 hipError_t apex_interp(pic_ctx* c, const double* phi, double X, double Y, double Z, double* out_dev);
+// profiling: tic returns a handle for toc (or -1 when profiling is off)
+int tic(pic_ctx* c, int slot);
+void toc(pic_ctx* c, int h);
+void flush_timers(pic_ctx* c);
 }  // namespace pic

@@ -71,7 +71,8 @@ class pic_moments_t(C.Structure):
                 ("events", C.c_int64 * 5), ("injected", C.c_int64), ("fn_clamped", C.c_int64),
                 ("bsi_count", C.c_int64), ("q_total", C.c_int64), ("next_id", C.c_int64), ("step", C.c_int64),
                 ("ke", C.c_double * 3), ("i_sr", C.c_double), ("fn_expected", C.c_double), ("v0", C.c_double),
-                ("apex_field1", C.c_double), ("error", C.c_int32), ("pad", C.c_int32)]
+                ("apex_field1", C.c_double), ("error", C.c_int32), ("last_cg_iters", C.c_int32),
+                ("last_cg_relres", C.c_double), ("cg_iters_total", C.c_int64)]
 
 
 class pic_event(C.Structure):
@@ -97,6 +98,10 @@ def lib():
         L.pic_solve_poisson.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_int32, C.POINTER(pic_solve_info)]
         L.pic_moments.argtypes = [vp, C.POINTER(pic_moments_t)]
         L.pic_events.argtypes = [vp, C.POINTER(pic_event), C.c_int64, C.POINTER(C.c_int64)]
+        L.pic_profile.argtypes = [vp, C.c_int32]
+        L.pic_timers.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32]
+        L.pic_profile.restype = C.c_int32
+        L.pic_timers.restype = C.c_int32
         L.pic_last_error.argtypes = [vp]
         L.pic_last_error.restype = C.c_char_p
         L.pic_destroy.argtypes = [vp]
@@ -159,7 +164,8 @@ def pic_moments(ctx) -> dict:
             "absorbed": np.array([list(r) for r in m.absorbed]), "events": np.array(m.events[:]),
             "injected": m.injected, "fn_clamped": m.fn_clamped, "bsi_count": m.bsi_count, "q_total": m.q_total,
             "next_id": m.next_id, "step": m.step, "ke": np.array(m.ke[:]), "i_sr": m.i_sr,
-            "fn_expected": m.fn_expected, "v0": m.v0, "apex_field1": m.apex_field1, "error": m.error}
+            "fn_expected": m.fn_expected, "v0": m.v0, "apex_field1": m.apex_field1, "error": m.error,
+            "last_cg_iters": m.last_cg_iters, "last_cg_relres": m.last_cg_relres, "cg_iters_total": m.cg_iters_total}
 
 
 def pic_events(ctx, cap: int) -> list:
@@ -168,6 +174,20 @@ def pic_events(ctx, cap: int) -> list:
     _check(lib().pic_events(ctx, buf, cap, C.byref(n)), ctx)
     m = min(n.value, cap)
     return [(buf[i].kind, buf[i].id_a, buf[i].id_b, buf[i].new_ion, buf[i].new_e) for i in range(m)]
+
+
+TIMERS = ("inject", "push_e", "push", "particles", "collide", "mcc", "solve", "cg_a", "cg_b", "step", "mg", "spare")
+
+
+def pic_profile(ctx, enable: bool):
+    _check(lib().pic_profile(ctx, 1 if enable else 0), ctx)
+
+
+def pic_timers(ctx, reset: bool = True) -> dict:
+    ms = (C.c_double * 12)()
+    cnt = (C.c_int64 * 12)()
+    _check(lib().pic_timers(ctx, ms, cnt, 1 if reset else 0), ctx)
+    return {name: (ms[i], cnt[i]) for i, name in enumerate(TIMERS)}
 
 
 def pic_last_error(ctx) -> str:
