@@ -99,7 +99,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="gpu_scale", choices=["gpu_scale", "tiny"])
-    ap.add_argument("--solver", default="cg", choices=["cg", "mgcg", "mixed"])
+    ap.add_argument("--solver", default="mgcg", choices=["cg", "mgcg", "mixed"])
     ap.add_argument("--sort-every", type=int, default=16)
     ap.add_argument("--cpu-sample", type=int, default=3_000_000)
     ap.add_argument("--cpu-steps", type=int, default=5)

@@ -226,7 +226,9 @@ pic_status pic_events(pic_ctx* ctx, pic_event* out, int64_t cap, int64_t* n);
 #define PIC_T_CG_B 8          /* CG kernel: x and r update, r.r */
 #define PIC_T_STEP 9          /* whole steps of pic_step */
 #define PIC_T_MG 10           /* multigrid V-cycles */
-#define PIC_NTIMERS 12
+#define PIC_T_DEPOSIT 11      /* tiled charge deposit kernel */
+#define PIC_T_BIN 12          /* cell bins (radix sort of the cell keys) */
+#define PIC_NTIMERS 13
 
 pic_status pic_profile(pic_ctx* ctx, int32_t enable);
 /* ms[PIC_NTIMERS]: summed milliseconds; count[PIC_NTIMERS]: number of timed

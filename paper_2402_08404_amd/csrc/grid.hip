@@ -286,11 +286,11 @@ __global__ __launch_bounds__(kBlock) void k_cg_resid(CgArgs a) {
     int64_t b1 = b0 + a.chunk < g.nn ? b0 + a.chunk : g.nn;
     int64_t pl = (int64_t)g.nx * g.ny;
     double bb = 0.0, rr = 0.0;
-    for (int64_t n = b0 + threadIdx.x; n < b1; n += blockDim.x) {
+    NodeWalk wk(b0 + threadIdx.x, blockDim.x, g.nx, g.ny);
+    for (int64_t n = b0 + threadIdx.x; n < b1; n += blockDim.x, wk.advance()) {
         ((double*)a.p_old)[n] = 0.0;
         if (a.type[n] != 0) continue;
-        int i, j, k;
-        node_ijk(g, n, i, j, k);
+        int i = wk.i, j = wk.j, k = wk.k;
         double fx = half_at_edge(j, g.ny) * half_at_edge(k, g.nz);
         double fy = half_at_edge(i, g.nx) * half_at_edge(k, g.nz);
         double fz = half_at_edge(i, g.nx) * half_at_edge(j, g.ny);
@@ -350,14 +350,14 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(CgArgs a, int it) {
     int64_t b1 = b0 + a.chunk < g.nn ? b0 + a.chunk : g.nn;
     int64_t pl = (int64_t)g.nx * g.ny;
     double pq = 0.0;
-    for (int64_t n = b0 + threadIdx.x; n < b1; n += blockDim.x) {
+    NodeWalk wk(b0 + threadIdx.x, blockDim.x, g.nx, g.ny);
+    for (int64_t n = b0 + threadIdx.x; n < b1; n += blockDim.x, wk.advance()) {
         if (a.type[n] != 0) {
             a.p_new[n] = 0.0;
             a.q[n] = 0.0;
             continue;
         }
-        int i, j, k;
-        node_ijk(g, n, i, j, k);
+        int i = wk.i, j = wk.j, k = wk.k;
         double fx = half_at_edge(j, g.ny) * half_at_edge(k, g.nz);
         double fy = half_at_edge(i, g.nx) * half_at_edge(k, g.nz);
         double fz = half_at_edge(i, g.nx) * half_at_edge(j, g.ny);
@@ -463,6 +463,145 @@ int cg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess, 
         if (hipStreamSynchronize(c->stream) != hipSuccess) return -2;
         if (c->host_st->done || launched > maxit) break;
         if (chunk < 64) chunk *= 2;
+    }
+    hipLaunchKernelGGL(k_cg_zero_free, dim3((unsigned)G), dim3(kBlock), 0, c->stream, g, c->buf.node_type, phi,
+                       c->st);
+    (void)hipMemcpyAsync(c->host_st, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return -2;
+    const DevState* h = c->host_st;
+    double bn = sqrt(h->bb);
+    info->iterations = h->it;
+    info->relres = h->zero_solution ? 0.0 : sqrt(h->rr) / bn;
+    info->relres0 = h->zero_solution ? 0.0 : sqrt(h->rr0) / bn;
+    info->converged = h->zero_solution || (sqrt(h->rr) <= rtol * bn);
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+// CG preconditioned by the multigrid V-cycle (z = M r). Per iteration: the
+// V-cycle (its first kernel finishes r.r and tests convergence, its last
+// writes the partials of r.z), then k_pcg_a (beta from r.z, p = z + beta p,
+// q = A p, partials of p.q) and k_pcg_b (alpha, x and r update, partials of
+// r.r).
+
+__global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs a, const double* __restrict__ z, const double* part_rz,
+                                                   int it) {
+    DevState* s = a.s;
+    if (s->done) return;
+    const Grid& g = a.g;
+    double rz = sum_partials(part_rz);
+    double beta = it == 0 ? 0.0 : rz / s->rzbuf[(it - 1) & 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s->rzbuf[it & 1] = rz;
+        s->it = it;
+    }
+    int64_t b0 = xcd_block(blockIdx.x, gridDim.x) * a.chunk;
+    int64_t b1 = b0 + a.chunk < g.nn ? b0 + a.chunk : g.nn;
+    int64_t pl = (int64_t)g.nx * g.ny;
+    double pq = 0.0;
+    NodeWalk wk(b0 + threadIdx.x, blockDim.x, g.nx, g.ny);
+    for (int64_t n = b0 + threadIdx.x; n < b1; n += blockDim.x, wk.advance()) {
+        if (a.type[n] != 0) {
+            a.p_new[n] = 0.0;
+            a.q[n] = 0.0;
+            continue;
+        }
+        int i = wk.i, j = wk.j, k = wk.k;
+        double fx = half_at_edge(j, g.ny) * half_at_edge(k, g.nz);
+        double fy = half_at_edge(i, g.nx) * half_at_edge(k, g.nz);
+        double fz = half_at_edge(i, g.nx) * half_at_edge(j, g.ny);
+        double pi = z[n] + beta * a.p_old[n];
+        double acc = 0.0;
+        int64_t nb[6] = {n - 1, n + 1, n - g.nx, n + g.nx, n - pl, n + pl};
+        bool has[6] = {i > 0, i < g.nx - 1, j > 0, j < g.ny - 1, true, true};
+        double f[6] = {fx, fx, fy, fy, fz, fz};
+#pragma unroll
+        for (int d = 0; d < 6; ++d) {
+            if (!has[d]) continue;
+            int64_t m = nb[d];
+            double pj = (a.type[m] == 0) ? z[m] + beta * a.p_old[m] : 0.0;
+            acc += f[d] * (pi - pj);
+        }
+        a.p_new[n] = pi;
+        a.q[n] = acc;
+        pq += pi * acc;
+    }
+    write_partial(pq, a.part_pq);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pcg_b(CgArgs a, int it) {
+    DevState* s = a.s;
+    if (s->done) return;
+    const Grid& g = a.g;
+    double pq = sum_partials(a.part_pq);
+    double alpha = s->rzbuf[it & 1] / pq;
+    int64_t b0 = xcd_block(blockIdx.x, gridDim.x) * a.chunk;
+    int64_t b1 = b0 + a.chunk < g.nn ? b0 + a.chunk : g.nn;
+    double rr = 0.0;
+    for (int64_t n = b0 + threadIdx.x; n < b1; n += blockDim.x) {
+        if (a.type[n] != 0) continue;
+        double p = a.p_new[n];
+        a.x[n] += alpha * p;
+        double r = a.r[n] - alpha * a.q[n];
+        a.r[n] = r;
+        rr += r * r;
+    }
+    write_partial(rr, a.part_rr);
+    if (blockIdx.x == 0 && threadIdx.x == 0) s->it = it + 1;
+}
+
+int mgcg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess, double rtol, int maxit,
+               pic_solve_info* info) {
+    if (!c->mg_host) return -3;
+    const Grid& g = c->g;
+    int64_t G = (g.nn + kBlock - 1) / kBlock;
+    CgArgs a;
+    a.g = g;
+    a.type = c->buf.node_type;
+    a.x = phi;
+    a.r = c->cg_r;
+    a.p_old = c->cg_p0;
+    a.p_new = c->cg_p1;
+    a.q = c->cg_q;
+    a.rho = rho;
+    a.qscale = ldexp(1.0, -40) * kQe / (kEps0 * g.h);
+    a.V0 = V0;
+    a.s = c->st;
+    a.part_pq = c->partials;
+    a.part_rr = c->partials + kCgBlocks;
+    a.part_bb = c->partials + 2 * kCgBlocks;
+    double* part_rz = c->partials + 3 * kCgBlocks;
+    a.chunk = ((g.nn + kCgBlocks - 1) / kCgBlocks + kBlock - 1) / kBlock * kBlock;
+    hipLaunchKernelGGL(k_cg_setup, dim3(1), dim3(1), 0, c->stream, c->st, rtol, maxit);
+    hipLaunchKernelGGL(k_cg_init, dim3((unsigned)G), dim3(kBlock), 0, c->stream, a, guess == PIC_GUESS_ZERO);
+    hipLaunchKernelGGL(k_cg_resid, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a);
+    double* pa = c->cg_p0;
+    double* pb = c->cg_p1;
+    int chunk = 2;
+    int it = 0;
+    while (true) {
+        for (int t = 0; t < chunk && it <= maxit; ++t, ++it) {
+            int tm = it < 64 ? tic(c, PIC_T_MG) : -1;
+            double* z = mg_vcycle(c, a.part_rr, a.part_bb, part_rz, kCgBlocks);
+            toc(c, tm);
+            if (it == maxit) continue;
+            a.p_old = pa;
+            a.p_new = pb;
+            int ta = it < 64 ? tic(c, PIC_T_CG_A) : -1;
+            hipLaunchKernelGGL(k_pcg_a, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a, (const double*)z,
+                               (const double*)part_rz, it);
+            toc(c, ta);
+            int tb = it < 64 ? tic(c, PIC_T_CG_B) : -1;
+            hipLaunchKernelGGL(k_pcg_b, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a, it);
+            toc(c, tb);
+            double* t2 = pa;
+            pa = pb;
+            pb = t2;
+        }
+        (void)hipMemcpyAsync(c->host_st, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream);
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return -2;
+        if (c->host_st->done || it > maxit) break;
+        if (chunk < 16) chunk *= 2;
     }
     hipLaunchKernelGGL(k_cg_zero_free, dim3((unsigned)G), dim3(kBlock), 0, c->stream, g, c->buf.node_type, phi,
                        c->st);

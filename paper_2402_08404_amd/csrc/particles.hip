@@ -11,16 +11,14 @@ namespace pic {
 // x^{n+1} = x^n + v^{n+1/2} dt (neutrals drift); particles that end outside
 // the vacuum region are removed. Fused with the rest of the per-particle pass
 // over x^{n+1}:
-//  - the charge deposit (source of Eq. poi): CIC weights quantized per axis to
-//    2^-13, 2^-13, 2^-14 so each product is an integer number of 2^-40 e,
-//    accumulated with int64 atomics (order independent, hence deterministic);
 //  - the cell key and the particle's slot among the particles of its cell;
 //  - for neutrals, the field-ionization test of Eq. dfi at x^{n+1} (the draw
 //    is keyed by particle id and step, so the test can run here; whether the
 //    neutral is free to ionize is decided after the collisions);
 //  - the largest speed per species (bound for the null-collision test).
-// Products of ionization carry +e and -e at the same point, so depositing
-// before the collisions gives the same node charge as after them.
+// The charge deposit follows from the cell bins (k_deposit_tiles). Products
+// of ionization carry +e and -e at the same point, so depositing before the
+// collisions gives the same node charge as after them.
 
 template <typename T>
 struct PushArgs {
@@ -30,9 +28,7 @@ struct PushArgs {
     T kq;
     int64_t* rho;
     int64_t sign;
-    uint32_t* cnt;
     uint32_t* key;
-    uint32_t* slot;
     DevState* st;
     uint32_t step;
     uint64_t seed;
@@ -74,6 +70,10 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs<T> a) {
     const int64_t n = (int64_t)a.st->n_slots[SP];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     unsigned int smax = 0;
+    // removals per boundary and neutrals above the barrier-suppression field:
+    // counted per thread, reduced per block (one atomic per block and kind)
+    unsigned int lost[5] = {0, 0, 0, 0, 0};
+    unsigned int bsi = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         uint32_t id = a.s.id[i];
         if (id == kDead) {
@@ -105,50 +105,33 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs<T> a) {
         if (code != 0) {
             a.s.id[i] = kDead;
             a.key[i] = kDead;
-            atomicAdd(&a.st->absorbed[SP][code], 1ull);
+            lost[code]++;
             continue;
         }
         int ci = clampi((int)floor(Xd), 0, g.nx - 2);
         int cj = clampi((int)floor(Yd), 0, g.ny - 2);
         int ck = clampi((int)floor(Zd), 0, g.nz - 2);
-        uint32_t cell = (uint32_t)(((int64_t)ck * (g.ny - 1) + cj) * (g.nx - 1) + ci);
-        a.key[i] = cell;
-        a.slot[i] = atomicAdd(&a.cnt[cell], 1u);
+        a.key[i] = cell_key(g, ci, cj, ck);
         double vx = (double)VX, vy = (double)VY, vz = (double)VZ;
         unsigned int sb = speed_bits(sqrt(vx * vx + vy * vy + vz * vz));
         smax = sb > smax ? sb : smax;
-        if (SP != PIC_NEUTRAL) {
-            int64_t qx = quantize(Xd - ci, 13), qy = quantize(Yd - cj, 13), qz = quantize(Zd - ck, 14);
-            int64_t wx0 = 8192 - qx, wy0 = 8192 - qy, wz0 = 16384 - qz;
-            int64_t n0 = ((int64_t)ck * g.ny + cj) * g.nx + ci;
-            int64_t pl = (int64_t)g.nx * g.ny;
-            unsigned long long* q = (unsigned long long*)a.rho;
-            int64_t s = a.sign;
-            atomicAdd(q + n0, (unsigned long long)(s * wx0 * wy0 * wz0));
-            atomicAdd(q + n0 + 1, (unsigned long long)(s * qx * wy0 * wz0));
-            atomicAdd(q + n0 + g.nx, (unsigned long long)(s * wx0 * qy * wz0));
-            atomicAdd(q + n0 + g.nx + 1, (unsigned long long)(s * qx * qy * wz0));
-            atomicAdd(q + n0 + pl, (unsigned long long)(s * wx0 * wy0 * qz));
-            atomicAdd(q + n0 + pl + 1, (unsigned long long)(s * qx * wy0 * qz));
-            atomicAdd(q + n0 + pl + g.nx, (unsigned long long)(s * wx0 * qy * qz));
-            atomicAdd(q + n0 + pl + g.nx + 1, (unsigned long long)(s * qx * qy * qz));
-        } else {
+        if (SP == PIC_NEUTRAL) {
             // Field ionization of Eq. dfi: rate per fs at the local field in
             // GV/m; no attempt above the barrier-suppression field.
             T ex, ey, ez;
             gather<T>(g, a.field, X, Y, Z, ex, ey, ez);
             double exd = (double)ex, eyd = (double)ey, ezd = (double)ez;
             double Eg = sqrt(exd * exd + eyd * eyd + ezd * ezd) * 1e-9;
+            bool cand = false;
             if (Eg > a.ebsi) {
-                atomicAdd(&a.st->bsi_count, 1ull);
+                bsi++;
             } else if (Eg > a.fi_thr) {
                 double pdt = a.adk_c * pow(20.5 * a.x32 / Eg, a.adk_e) * exp(-6.83 * a.x32 / Eg) * a.dt_fs;
                 Draw2 u = draw2(a.seed, id, a.step, kTagFi, 0);
-                if (pdt > u.a) {
-                    unsigned long long p = atomicAdd(&a.st->n_fi, 1ull);
-                    a.fi_list[p] = (uint32_t)i;
-                }
+                cand = pdt > u.a;
             }
+            unsigned long long p = wave_append(&a.st->n_fi, cand);
+            if (cand) a.fi_list[p] = (uint32_t)i;
         }
     }
     // largest speed of the species
@@ -158,19 +141,76 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs<T> a) {
         smax = v > smax ? v : smax;
     }
     if (lane_id() == 0 && smax) atomicMax(&a.st->smax_bits[SP], smax);
+    __shared__ unsigned int sh[kBlock / 64];
+    for (int k = 1; k < 5; ++k) {
+        unsigned int t = block_sum(lost[k], sh);
+        if (threadIdx.x == 0 && t) atomicAdd(&a.st->absorbed[SP][k], (unsigned long long)t);
+    }
+    if (SP == PIC_NEUTRAL) {
+        unsigned int t = block_sum(bsi, sh);
+        if (threadIdx.x == 0 && t) atomicAdd(&a.st->bsi_count, (unsigned long long)t);
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Cell bins: bins[off[cell] + slot] = species << 30 | index.
+// Charge deposit, the source of Eq. poi: CIC weights of x^{n+1} quantized per
+// axis to 2^-13, 2^-13 and 2^-14, so every product is an integer number of
+// 2^-40 e and the eight corners of a particle sum to 2^40 exactly. One
+// workgroup per tile of 8^3 cells reads the tile's particles from the cell
+// bins, accumulates the (8+1)^3 nodes of the tile in LDS with 64-bit LDS
+// atomics, then adds each touched node to global memory with one atomic.
+// Integer sums do not depend on order, so the result is deterministic.
 
-__global__ void k_scatter(int sp, const uint32_t* __restrict__ key, const uint32_t* __restrict__ slot,
-                          const uint32_t* __restrict__ off, uint32_t* __restrict__ bins, const DevState* st) {
-    int64_t n = (int64_t)st->n_push[sp];
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        uint32_t k = key[i];
-        if (k == kDead) continue;
-        bins[off[k] + slot[i]] = ((uint32_t)sp << 30) | (uint32_t)i;
+template <typename T>
+struct DepositArgs {
+    Species<T> e, ion;
+    const uint32_t* off;
+    const uint32_t* bins;
+    int64_t* rho;
+    Grid g;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_deposit_tiles(DepositArgs<T> a) {
+    constexpr int N1 = kTile + 1;
+    __shared__ unsigned long long q[N1 * N1 * N1];
+    const Grid& g = a.g;
+    uint32_t tile = blockIdx.x;
+    uint32_t b0 = a.off[(int64_t)tile * kTileCells], b1 = a.off[(int64_t)(tile + 1) * kTileCells];
+    if (b0 == b1) return;
+    int tx = (int)(tile % g.ntx), ty = (int)((tile / g.ntx) % g.nty), tz = (int)(tile / (g.ntx * g.nty));
+    int ox = tx * kTile, oy = ty * kTile, oz = tz * kTile;
+    for (int m = threadIdx.x; m < N1 * N1 * N1; m += blockDim.x) q[m] = 0ull;
+    __syncthreads();
+    for (uint32_t b = b0 + threadIdx.x; b < b1; b += blockDim.x) {
+        uint32_t e = a.bins[b];
+        uint32_t s = e >> 30;
+        if (s == PIC_NEUTRAL) continue;
+        uint32_t i = e & 0x3FFFFFFFu;
+        const Species<T>& P = s == PIC_ELECTRON ? a.e : a.ion;
+        double X = (double)P.x[i], Y = (double)P.y[i], Z = (double)P.z[i];
+        int ci = clampi((int)floor(X), 0, g.nx - 2), cj = clampi((int)floor(Y), 0, g.ny - 2),
+            ck = clampi((int)floor(Z), 0, g.nz - 2);
+        int64_t qx = quantize(X - ci, 13), qy = quantize(Y - cj, 13), qz = quantize(Z - ck, 14);
+        int64_t sg = s == PIC_ELECTRON ? -1 : 1;
+        int64_t w[2][3] = {{8192 - qx, 8192 - qy, 16384 - qz}, {qx, qy, qz}};
+        int lx = ci - ox, ly = cj - oy, lz = ck - oz;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            int dx = t & 1, dy = (t >> 1) & 1, dz = (t >> 2) & 1;
+            int64_t v = sg * w[dx][0] * w[dy][1] * w[dz][2];
+            atomicAdd(&q[((lz + dz) * N1 + (ly + dy)) * N1 + (lx + dx)], (unsigned long long)v);
+        }
+    }
+    __syncthreads();
+    unsigned long long* rho = (unsigned long long*)a.rho;
+    for (int m = threadIdx.x; m < N1 * N1 * N1; m += blockDim.x) {
+        unsigned long long v = q[m];
+        if (v == 0ull) continue;
+        int lx = m % N1, ly = (m / N1) % N1, lz = m / (N1 * N1);
+        int i = ox + lx, j = oy + ly, k = oz + lz;
+        if (i >= g.nx || j >= g.ny || k >= g.nz) continue;
+        atomicAdd(rho + ((int64_t)k * g.ny + j) * g.nx + i, v);
     }
 }
 
@@ -192,9 +232,10 @@ __global__ void k_scatter(int sp, const uint32_t* __restrict__ key, const uint32
 template <typename T>
 struct MccArgs {
     Species<T> sp[3];
+    Grid g;
     const uint32_t* off;
     uint32_t* bins;
-    int64_t nc;
+    int64_t nc;  // number of cell keys
     uint32_t* big;
     DevState* st;
     uint32_t step;
@@ -213,6 +254,13 @@ struct MccArgs {
     int64_t ev_cap;
     int record, write_sorted;
 };
+
+// Linear index of the cell with this key: the per-cell draw is keyed by it.
+__device__ inline uint32_t linear_cell(const Grid& g, uint32_t key) {
+    int i, j, k;
+    key_cell(g, key, i, j, k);
+    return (uint32_t)(((int64_t)k * (g.ny - 1) + j) * (g.nx - 1) + i);
+}
 
 __device__ inline double xs_lookup(const double* tab, int n, double emin, double lnr, double E) {
     if (E <= emin) return tab[0];
@@ -342,9 +390,8 @@ __device__ int resolve_pair(const MccArgs<T>& a, int cls, uint32_t pid, uint32_t
     a.prod_ve[3 * (int64_t)ib + 1] = (vn[1] + w2 * s2[1]) * g;
     a.prod_ve[3 * (int64_t)ib + 2] = (vn[2] + w2 * s2[2]) * g;
     atomicOr(&a.bitmap_imp[idB >> 5], 1u << (idB & 31));
-    unsigned long long p = atomicAdd(&a.st->n_prod, 1ull);
-    a.prod_list[p] = ib;  // kind 0 (impact)
-    atomicAdd(&a.st->n_prod_kind[0], 1ull);
+    unsigned long long p = wave_append(&a.st->n_prod, true);
+    a.prod_list[p] = ib;  // kind 0 (impact); n_prod_kind[0] is added per block
     a.prod_ev[ib] = (int32_t)record_event(a, PIC_EV_IONIZE, idA, idB);
     return PIC_EV_IONIZE;
 }
@@ -368,7 +415,7 @@ __device__ void cell_class_seq(const MccArgs<T>& a, int cls, uint32_t cell, cons
     bool a_proj = na <= nb;
     int P0 = a_proj ? a0 : b0, NP = a_proj ? na : nb;
     int T0 = a_proj ? b0 : a0, NT = a_proj ? nb : na;
-    Draw2 dc = draw2(a.seed, cell, a.step, cls == 1 ? kTagPair1 : kTagPair2, 0);
+    Draw2 dc = draw2(a.seed, linear_cell(a.g, cell), a.step, cls == 1 ? kTagPair1 : kTagPair2, 0);
     int shift = (int)floor(dc.a * (double)NT);
     shift = shift > NT - 1 ? NT - 1 : shift;
     double pnull = pnull_of(a, cls, NT);
@@ -392,7 +439,10 @@ __device__ inline void flush_counts(DevState* st, int cnt[5]) {
     __shared__ int sh[kBlock / 64];
     for (int k = 1; k <= 3; ++k) {
         int t = block_sum(cnt[k], sh);
-        if (threadIdx.x == 0 && t) atomicAdd(&st->events[k], (unsigned long long)t);
+        if (threadIdx.x == 0 && t) {
+            atomicAdd(&st->events[k], (unsigned long long)t);
+            if (k == PIC_EV_IONIZE) atomicAdd(&st->n_prod_kind[0], (unsigned long long)t);
+        }
     }
 }
 
@@ -512,7 +562,7 @@ __global__ __launch_bounds__(64) void k_mcc_big(MccArgs<T> a) {
                 bool a_proj = na <= nb;
                 int P0 = a_proj ? a0 : b0, NP = a_proj ? na : nb;
                 int T0 = a_proj ? b0 : a0, NT = a_proj ? nb : na;
-                Draw2 dc = draw2(a.seed, c, a.step, cls == 1 ? kTagPair1 : kTagPair2, 0);
+                Draw2 dc = draw2(a.seed, linear_cell(a.g, c), a.step, cls == 1 ? kTagPair1 : kTagPair2, 0);
                 int shift = (int)floor(dc.a * (double)NT);
                 shift = shift > NT - 1 ? NT - 1 : shift;
                 double pnull = pnull_of(a, cls, NT);
@@ -534,7 +584,10 @@ __global__ __launch_bounds__(64) void k_mcc_big(MccArgs<T> a) {
     }
     for (int k = 1; k <= 3; ++k) {
         int t = wave_sum(cnt[k]);
-        if (lane == 0 && t) atomicAdd(&a.st->events[k], (unsigned long long)t);
+        if (lane == 0 && t) {
+            atomicAdd(&a.st->events[k], (unsigned long long)t);
+            if (k == PIC_EV_IONIZE) atomicAdd(&a.st->n_prod_kind[0], (unsigned long long)t);
+        }
     }
 }
 
@@ -547,22 +600,25 @@ __global__ void k_fi_resolve(MccArgs<T> a, const uint32_t* fi_list, uint32_t* bi
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         uint32_t ib = fi_list[i];
-        if (a.nflag[ib] == a.step + 1u) continue;
+        bool go = a.nflag[ib] != a.step + 1u;
+        unsigned long long p = wave_append(&a.st->n_prod, go);
+        if (!go) continue;
         a.nflag[ib] = a.step + 1u;
         uint32_t id = N.id[ib];
         atomicOr(&bitmap_fi[id >> 5], 1u << (id & 31));
         a.prod_ve[3 * (int64_t)ib + 0] = (double)N.vx[ib];
         a.prod_ve[3 * (int64_t)ib + 1] = (double)N.vy[ib];
         a.prod_ve[3 * (int64_t)ib + 2] = (double)N.vz[ib];
-        unsigned long long p = atomicAdd(&a.st->n_prod, 1ull);
         a.prod_list[p] = ib | 0x80000000u;
-        atomicAdd(&a.st->n_prod_kind[1], 1ull);
         a.prod_ev[ib] = (int32_t)record_event(a, PIC_EV_FIELD_ION, kDead, id);
         ++cnt;
     }
     __shared__ int sh[kBlock / 64];
     int t = block_sum(cnt, sh);
-    if (threadIdx.x == 0 && t) atomicAdd(&a.st->events[PIC_EV_FIELD_ION], (unsigned long long)t);
+    if (threadIdx.x == 0 && t) {
+        atomicAdd(&a.st->events[PIC_EV_FIELD_ION], (unsigned long long)t);
+        atomicAdd(&a.st->n_prod_kind[1], (unsigned long long)t);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -790,12 +846,33 @@ static unsigned grid_for(int64_t n) {
     return (unsigned)g;
 }
 
+// Cell bins (radix sort of the keys), then the deposit.
+template <typename T>
+static hipError_t bin_t(pic_ctx* c) {
+    const Grid& g = c->g;
+    int tb = tic(c, PIC_T_BIN);
+    hipError_t e = radix_bins(c);
+    toc(c, tb);
+    if (e != hipSuccess) return e;
+    DepositArgs<T> d;
+    d.e = species<T>(c, PIC_ELECTRON);
+    d.ion = species<T>(c, PIC_ION);
+    d.off = c->off;
+    d.bins = c->bins;
+    d.rho = c->buf.rho;
+    d.g = g;
+    int td = tic(c, PIC_T_DEPOSIT);
+    hipLaunchKernelGGL(k_deposit_tiles<T>, dim3((unsigned)(g.nkeys / kTileCells)), dim3(kBlock), 0, c->stream, d);
+    toc(c, td);
+    c->bins_valid = 1;
+    return hipGetLastError();
+}
+
 template <typename T>
 static hipError_t particles_t(pic_ctx* c, bool move) {
     const pic_config& cf = c->cfg;
     hipLaunchKernelGGL(k_step_reset, dim3(1), dim3(1), 0, c->stream, c->st);
     (void)launch_zero(c->buf.rho, sizeof(int64_t) * c->g.nn, c->stream);
-    if (c->bins_dirty) (void)launch_zero(c->cnt, sizeof(uint32_t) * c->g.nc, c->stream);
     for (int s = 0; s < 3; ++s) {
         PushArgs<T> a;
         a.s = species<T>(c, s);
@@ -804,9 +881,7 @@ static hipError_t particles_t(pic_ctx* c, bool move) {
         a.kq = (T)c->kq[s];
         a.rho = c->buf.rho;
         a.sign = s == PIC_ELECTRON ? -1 : 1;
-        a.cnt = c->cnt;
         a.key = c->key[s];
-        a.slot = c->slot[s];
         a.st = c->st;
         a.step = (uint32_t)c->step;
         a.seed = cf.seed;
@@ -833,9 +908,7 @@ static hipError_t particles_t(pic_ctx* c, bool move) {
         if (s == 2) toc(c, c->push_all_handle);
         if (s == 0) c->push_all_handle = t_all;
     }
-    c->bins_dirty = 1;
-    c->bins_valid = 1;
-    return hipGetLastError();
+    return bin_t<T>(c);
 }
 
 hipError_t particles_phase(pic_ctx* c, bool move) {
@@ -846,20 +919,15 @@ template <typename T>
 static hipError_t collide_t(pic_ctx* c, bool record) {
     const pic_config& cf = c->cfg;
     const Grid& g = c->g;
-    // cell offsets (and counters cleared for the next pass), then the bins
-    hipError_t e = scan_u32(c, c->cnt, c->off, g.nc, nullptr, c->off + g.nc, true, false);
-    if (e != hipSuccess) return e;
-    c->bins_dirty = 0;
-    for (int s = 0; s < 3; ++s)
-        hipLaunchKernelGGL(k_scatter, dim3(grid_for(c->buf.cap[s])), dim3(kBlock), 0, c->stream, s, c->key[s],
-                           c->slot[s], c->off, c->bins, c->st);
+    hipError_t e;
     bool resort = cf.sort_every > 0 && (c->need_sort || ((c->collide_count + 1) % cf.sort_every) == 0);
     c->need_sort = 0;
     MccArgs<T> a;
     for (int s = 0; s < 3; ++s) a.sp[s] = species<T>(c, s);
+    a.g = g;
     a.off = c->off;
     a.bins = c->bins;
-    a.nc = g.nc;
+    a.nc = g.nkeys;
     a.big = c->big;
     a.st = c->st;
     a.step = (uint32_t)c->step;
@@ -884,7 +952,7 @@ static hipError_t collide_t(pic_ctx* c, bool record) {
     a.record = record ? 1 : 0;
     a.write_sorted = resort ? 1 : 0;
     int tm = tic(c, PIC_T_MCC);
-    hipLaunchKernelGGL(k_mcc_small<T>, dim3(grid_for(g.nc)), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(k_mcc_small<T>, dim3(grid_for(g.nkeys)), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(k_mcc_big<T>, dim3(1024), dim3(64), 0, c->stream, a);
     toc(c, tm);
     hipLaunchKernelGGL(k_fi_resolve<T>, dim3(grid_for(c->buf.cap[2])), dim3(kBlock), 0, c->stream, a, c->fi_list,
@@ -917,14 +985,14 @@ static hipError_t collide_t(pic_ctx* c, bool record) {
         int64_t capsum = c->buf.cap[0] + c->buf.cap[1] + c->buf.cap[2];
         for (int s = 0; s < 3; ++s) {
             hipLaunchKernelGGL(k_sort_flags, dim3(grid_for(capsum)), dim3(kBlock), 0, c->stream, s, c->bins,
-                               c->off + g.nc, (const uint32_t* const*)c->id_ptrs, flag, capsum);
-            e = scan_u32(c, flag, c->rank, capsum, c->off + g.nc, c->dyn + 1, false, false);
+                               c->off + g.nkeys, (const uint32_t* const*)c->id_ptrs, flag, capsum);
+            e = scan_u32(c, flag, c->rank, capsum, c->off + g.nkeys, c->dyn + 1, false, false);
             if (e != hipSuccess) return e;
             SortArgs<T> sa;
             sa.s = species<T>(c, s);
             sa.sp = s;
             sa.bins = c->bins;
-            sa.nbins = c->off + g.nc;
+            sa.nbins = c->off + g.nkeys;
             sa.flag = flag;
             sa.rank = c->rank;
             sa.total = c->dyn + 1;
@@ -1191,7 +1259,8 @@ constexpr int kMomBlocks = 512;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_moments(Species<T> s0, Species<T> s1, Species<T> s2,
                                                      const typename V4<T>::type* E0, Grid g, double sv, double m_ion,
-                                                     const DevState* st, double* part) {
+                                                     const DevState* st, double* part, const int64_t* rho,
+                                                     long long* qpart) {
     __shared__ double sh[kBlock / 64];
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
     const Species<T>* S[3] = {&s0, &s1, &s2};
@@ -1217,9 +1286,14 @@ __global__ __launch_bounds__(kBlock) void k_moments(Species<T> s0, Species<T> s1
         double t = block_sum(acc[k], sh);
         if (threadIdx.x == 0) part[blockIdx.x * 7 + k] = t;
     }
+    long long qs = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.nn; i += stride) qs += rho[i];
+    __shared__ long long shl[kBlock / 64];
+    long long tq = block_sum(qs, shl);
+    if (threadIdx.x == 0) qpart[blockIdx.x] = tq;
 }
 
-__global__ void k_moments_final(const double* part, int nb, const int64_t* rho, int64_t nn, double* out) {
+__global__ void k_moments_final(const double* part, int nb, const long long* qpart, double* out) {
     __shared__ double sh[kBlock / 64];
     for (int k = 0; k < 7; ++k) {
         double s = 0.0;
@@ -1229,7 +1303,7 @@ __global__ void k_moments_final(const double* part, int nb, const int64_t* rho, 
     }
     __shared__ long long shl[kBlock / 64];
     long long q = 0;
-    for (int64_t i = threadIdx.x; i < nn; i += blockDim.x) q += rho[i];
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) q += qpart[b];
     long long tq = block_sum(q, shl);
     if (threadIdx.x == 0) ((long long*)out)[7] = tq;
 }
@@ -1240,13 +1314,13 @@ hipError_t moments_phase(pic_ctx* c, double* out_dev) {
     if (c->cfg.precision == PIC_F32)
         hipLaunchKernelGGL(k_moments<float>, dim3(kMomBlocks), dim3(kBlock), 0, c->stream, species<float>(c, 0),
                            species<float>(c, 1), species<float>(c, 2), (const float4*)c->buf.field0, c->g, sv,
-                           c->cfg.m_ion, c->st, part);
+                           c->cfg.m_ion, c->st, part, c->buf.rho, (long long*)(part + 7 * kMomBlocks));
     else
         hipLaunchKernelGGL(k_moments<double>, dim3(kMomBlocks), dim3(kBlock), 0, c->stream, species<double>(c, 0),
                            species<double>(c, 1), species<double>(c, 2), (const double4*)c->buf.field0, c->g, sv,
-                           c->cfg.m_ion, c->st, part);
-    hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(kBlock), 0, c->stream, part, kMomBlocks, c->buf.rho, c->g.nn,
-                       out_dev);
+                           c->cfg.m_ion, c->st, part, c->buf.rho, (long long*)(part + 7 * kMomBlocks));
+    hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(kBlock), 0, c->stream, part, kMomBlocks,
+                       (const long long*)(part + 7 * kMomBlocks), out_dev);
     return hipGetLastError();
 }
 

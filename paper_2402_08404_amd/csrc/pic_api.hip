@@ -80,15 +80,16 @@ size_t pic::scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[
         return p;
     };
     int64_t nn = (int64_t)cfg->nx * cfg->ny * cfg->nz;
-    int64_t nc = (int64_t)(cfg->nx - 1) * (cfg->ny - 1) * (cfg->nz - 1);
+    int64_t ntiles = (int64_t)((cfg->nx - 2) / kTile + 1) * ((cfg->ny - 2) / kTile + 1) * ((cfg->nz - 2) / kTile + 1);
+    int64_t nc = ntiles * kTileCells;  // cell keys (tile-major numbering)
     int64_t capsum = cap[0] + cap[1] + cap[2];
     int64_t capmax = std::max(cap[0], std::max(cap[1], cap[2]));
     int64_t idc = id_capacity(cfg, cap);
     int64_t words = (idc + 31) / 32;
     size_t tsz = cfg->precision == PIC_F32 ? 4 : 8;
-    int64_t scan_n = std::max(nc + 1, std::max(capsum, words));
+    int64_t scan_n = std::max(std::max(nc + 1, 256 * ((capsum + 4095) / 4096 + 1)), std::max(capsum, words));
     int64_t scan_blocks = (scan_n + 4095) / 4096 + 1;
-    int64_t parts = std::max<int64_t>(2 * ((nn + kBlock - 1) / kBlock), 7 * 512) + 64;
+    int64_t parts = std::max<int64_t>(4 * 1024, 8 * 512) + 64;  // CG/MG partials (4 x 1024), moments (8 x 512)
     pic_ctx dummy;
     pic_ctx* t = c ? c : &dummy;
     t->st = (DevState*)take(sizeof(DevState));
@@ -96,13 +97,14 @@ size_t pic::scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[
     t->id_ptrs = (uint32_t**)take(3 * sizeof(uint32_t*));
     t->mom_out = (double*)take(16 * sizeof(double));
     t->xs = (double*)take(3 * (size_t)cfg->xs_n * sizeof(double));
-    t->cnt = (uint32_t*)take(nc * 4);
     t->off = (uint32_t*)take((nc + 1) * 4);
-    for (int s = 0; s < 3; ++s) {
-        t->key[s] = (uint32_t*)take(cap[s] * 4);
-        t->slot[s] = (uint32_t*)take(cap[s] * 4);
-    }
+    for (int s = 0; s < 3; ++s) t->key[s] = (uint32_t*)take(cap[s] * 4);
     t->bins = (uint32_t*)take(capsum * 4);
+    for (int k = 0; k < 2; ++k) {
+        t->rs_keys[k] = (uint32_t*)take(capsum * 4);
+        t->rs_vals[k] = (uint32_t*)take(capsum * 4);
+    }
+    t->rs_hist = (uint32_t*)take(256 * ((capsum + 4095) / 4096 + 1) * 4);
     t->big = (uint32_t*)take(nc * 4);
     t->fi_list = (uint32_t*)take(cap[2] * 4);
     t->nflag = (uint32_t*)take(cap[2] * 4);
@@ -192,6 +194,10 @@ pic_status pic_init(const pic_config* cfg, const pic_buffers* bufs, void* hip_st
     g.yc = 0.5 * (double)(cfg->ny - 1);
     g.nn = (int64_t)cfg->nx * cfg->ny * cfg->nz;
     g.nc = (int64_t)(cfg->nx - 1) * (cfg->ny - 1) * (cfg->nz - 1);
+    g.ntx = (cfg->nx - 2) / kTile + 1;
+    g.nty = (cfg->ny - 2) / kTile + 1;
+    g.ntz = (cfg->nz - 2) / kTile + 1;
+    g.nkeys = (int64_t)g.ntx * g.nty * g.ntz * kTileCells;
     const double qm[3] = {-kQe / kMe, kQe / cfg->m_ion, 0.0};
     for (int s = 0; s < 3; ++s) c->kq[s] = qm[s] * cfg->dt * cfg->dt / cfg->h;
     // ADK constants of Eq. dfi (z = 1) and the field below which P dt < 2^-64
@@ -241,11 +247,14 @@ pic_status pic_init(const pic_config* cfg, const pic_buffers* bufs, void* hip_st
     uint32_t* ids[3] = {bufs->id[0], bufs->id[1], bufs->id[2]};
     H(hipMemcpyAsync(c->id_ptrs, ids, sizeof(ids), hipMemcpyHostToDevice, c->stream), "copy id pointers");
     H(launch_zero(c->dyn, 64 * 4, c->stream), "zero");
-    H(launch_zero(c->cnt, g.nc * 4, c->stream), "zero");
     H(launch_zero(c->nflag, bufs->cap[2] * 4, c->stream), "zero");
     for (int k = 0; k < 2; ++k) H(launch_zero(c->bitmap[k], c->bm_words * 4, c->stream), "zero");
     H(launch_zero(bufs->rho, g.nn * 8, c->stream), "zero");
     H(launch_node_types(c), "node types");
+    if (st == PIC_OK) {
+        int r = mg_setup(c);
+        if (r == -2) st = fail(c, PIC_E_HIP, "multigrid setup failed");
+    }
     // unit-anode Laplace problem: phi1, its field (Shockley-Ramo weighting
     // field) and the anode voltage that gives the requested apex field
     pic_solve_info info{};
@@ -273,6 +282,7 @@ pic_status pic_init(const pic_config* cfg, const pic_buffers* bufs, void* hip_st
     if (st != PIC_OK) {
         g_init_error = c->err;
         (void)hipHostFree(c->host_st);
+        mg_free(c);
         delete c;
         return st;
     }
@@ -464,6 +474,7 @@ void pic_destroy(pic_ctx* c) {
         delete[] c->ev_slot;
     }
     if (c->host_st) (void)hipHostFree(c->host_st);
+    mg_free(c);
     delete c;
 }
 

@@ -44,18 +44,41 @@ struct DevState {
     int error;
     // CG scalars
     double rr, bb, rr0, pq, alpha, beta, rtol;
-    double rrbuf[2];
+    double rrbuf[2], rzbuf[2];
     int it, maxit, done, zero_solution;
     unsigned int red_count;
     // mixed-precision refinement
     double rr_outer;
 };
 
+// Cells are numbered tile-major: tiles of kTile^3 cells, tile index
+// (tz*nty + ty)*ntx + tx, then the cell inside the tile (lz*kTile + ly)*kTile
+// + lx. nkeys = ntiles * kTile^3 >= nc (edge tiles may be partial).
+constexpr int kTile = 8;
+constexpr int kTileCells = kTile * kTile * kTile;
+
 struct Grid {
     int nx, ny, nz;
     double h, R, H, zc, xc, yc;
     int64_t nn, nc;
+    int ntx, nty, ntz;
+    int64_t nkeys;
 };
+
+__host__ __device__ inline uint32_t cell_key(const Grid& g, int i, int j, int k) {
+    int tx = i / kTile, ty = j / kTile, tz = k / kTile;
+    uint32_t tile = (uint32_t)((tz * g.nty + ty) * g.ntx + tx);
+    return tile * (uint32_t)kTileCells + (uint32_t)(((k % kTile) * kTile + (j % kTile)) * kTile + (i % kTile));
+}
+
+// Cell (i, j, k) of a key; the linear cell index is (k*(ny-1) + j)*(nx-1) + i.
+__host__ __device__ inline void key_cell(const Grid& g, uint32_t key, int& i, int& j, int& k) {
+    uint32_t tile = key / kTileCells, l = key % kTileCells;
+    int tx = (int)(tile % g.ntx), ty = (int)((tile / g.ntx) % g.nty), tz = (int)(tile / (g.ntx * g.nty));
+    i = tx * kTile + (int)(l % kTile);
+    j = ty * kTile + (int)((l / kTile) % kTile);
+    k = tz * kTile + (int)(l / (kTile * kTile));
+}
 
 template <typename T>
 struct Species {
@@ -148,6 +171,45 @@ __device__ inline int64_t xcd_block(int64_t b, int64_t G) {
     return x * per + (x < rem ? x : rem) + t;
 }
 
+// Node coordinates along a strided walk n, n + step, n + 2 step, ... without
+// divisions: the step is decomposed once in base (ny, nx) and carried.
+struct NodeWalk {
+    int i, j, k;
+    int si, sj, sk, nx, ny;
+    __device__ NodeWalk(int64_t n, int step, int nx_, int ny_) : nx(nx_), ny(ny_) {
+        uint32_t n32 = (uint32_t)n, q = n32 / (uint32_t)nx;
+        i = (int)(n32 - q * (uint32_t)nx);
+        k = (int)(q / (uint32_t)ny);
+        j = (int)(q - (uint32_t)k * (uint32_t)ny);
+        si = step % nx;
+        sj = (step / nx) % ny;
+        sk = step / (nx * ny);
+    }
+    __device__ void advance() {
+        i += si;
+        int c = i >= nx;
+        i -= c * nx;
+        j += sj + c;
+        int c2 = j >= ny;
+        j -= c2 * ny;
+        k += sk + c2;
+    }
+};
+
+// Append from the active lanes with pred set: one atomic per wavefront,
+// slots in lane order. Every active lane of the wavefront must call it.
+__device__ inline unsigned long long wave_append(unsigned long long* ctr, bool pred) {
+    uint64_t mask = __ballot(pred);
+    if (mask == 0) return 0ull;
+    int lane = __lane_id();
+    int leader = __ffsll((unsigned long long)mask) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(ctr, (unsigned long long)__popcll(mask));
+    base = __shfl(base, leader, 64);
+    uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    return base + (unsigned long long)__popcll(mask & lt);
+}
+
 template <typename T>
 __device__ inline T wave_sum(T v) {
 #pragma unroll
@@ -189,12 +251,13 @@ struct pic_ctx {
     // scratch carve
     pic::DevState* st = nullptr;
     double* xs = nullptr;         // 3 * xs_n
-    uint32_t* cnt = nullptr;      // nc
-    uint32_t* off = nullptr;      // nc + 1
+    uint32_t* off = nullptr;      // nkeys + 1
     uint32_t* key[3] = {};
-    uint32_t* slot[3] = {};
     uint32_t* bins = nullptr;     // sum cap
-    uint32_t* big = nullptr;      // big-cell list (nc)
+    uint32_t* rs_keys[2] = {};    // radix sort ping-pong keys (sum cap)
+    uint32_t* rs_vals[2] = {};    // radix sort ping-pong values (sum cap)
+    uint32_t* rs_hist = nullptr;  // digit histograms
+    uint32_t* big = nullptr;      // big-cell list (nkeys)
     uint32_t* fi_list = nullptr;  // cap neutral
     uint32_t* nflag = nullptr;    // cap neutral: step+1 if the neutral had an event
     uint32_t* prod_list = nullptr;
@@ -216,12 +279,13 @@ struct pic_ctx {
     double *cg_r = nullptr, *cg_p0 = nullptr, *cg_p1 = nullptr, *cg_q = nullptr;
     double* partials = nullptr;
     int64_t partials_n = 0;
-    void* mg = nullptr;           // multigrid hierarchy (pic_mg.hip)
+    void* mg = nullptr;           // multigrid work memory
+    void* mg_host = nullptr;      // multigrid hierarchy (host description)
     void* mixed = nullptr;        // mixed-precision vectors
     // host state
     pic::DevState* host_st = nullptr;  // pinned mirror
     int64_t step = 0;
-    int bins_valid = 0, bins_dirty = 0, need_sort = 0;
+    int bins_valid = 0, need_sort = 0;
     int64_t collide_count = 0;
     int failed = 0;
     std::string err;
@@ -250,10 +314,13 @@ int mgcg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess
 int mixed_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess, double rtol, int maxit,
                 pic_solve_info* info);
 size_t mg_bytes(const pic_config* cfg);
+double* mg_vcycle(pic_ctx* c, double* part_rr, double* part_bb, double* part_rz, int cg_blocks);
+void mg_free(pic_ctx* c);
 hipError_t scan_u32(pic_ctx* c, const uint32_t* in, uint32_t* out, int64_t n_max, const uint32_t* nd,
                     uint32_t* total, bool zero_in, bool popcount);
 hipError_t particles_phase(pic_ctx* c, bool move);
 hipError_t collide_phase(pic_ctx* c, bool record);
+hipError_t radix_bins(pic_ctx* c);
 hipError_t inject_phase(pic_ctx* c);
 hipError_t load_particles(pic_ctx* c, const pic_particles* src);
 hipError_t moments_phase(pic_ctx* c, double* out_dev);
