@@ -370,7 +370,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_a(CgArgs a, int it) {
         for (int d = 0; d < 6; ++d) {
             if (!has[d]) continue;
             int64_t m = nb[d];
-            double pj = (a.type[m] == 0) ? a.r[m] + beta * a.p_old[m] : 0.0;
+            double pj = a.r[m] + beta * a.p_old[m];  // r and p are zero on fixed nodes
             acc += f[d] * (pi - pj);
         }
         a.p_new[n] = pi;
@@ -519,7 +519,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs a, const double* __rest
         for (int d = 0; d < 6; ++d) {
             if (!has[d]) continue;
             int64_t m = nb[d];
-            double pj = (a.type[m] == 0) ? z[m] + beta * a.p_old[m] : 0.0;
+            double pj = z[m] + beta * a.p_old[m];  // z and p are zero on fixed nodes
             acc += f[d] * (pi - pj);
         }
         a.p_new[n] = pi;

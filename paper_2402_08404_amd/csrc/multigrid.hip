@@ -135,7 +135,8 @@ __global__ void k_mg_build(MgLevel f, MgLevel c) {
 // ---------------------------------------------------------------------------
 // Operator application
 
-// Finest level, matrix free: returns (A x)_n and the diagonal.
+// Finest level, matrix free: returns (A x)_n and the diagonal. x must be zero
+// on nodes held at a fixed potential (true for every multigrid vector).
 __device__ inline double apply_fine(const Grid& g, const uint8_t* __restrict__ type, const double* __restrict__ x,
                                     int64_t n, int i, int j, int k, double xn, double* dg) {
     int64_t pl = (int64_t)g.nx * g.ny;
@@ -148,8 +149,7 @@ __device__ inline double apply_fine(const Grid& g, const uint8_t* __restrict__ t
     for (int q = 0; q < 6; ++q) {
         if (!has[q]) continue;
         d += f[q];
-        double xj = type[nb[q]] == 0 ? x[nb[q]] : 0.0;
-        acc += f[q] * (xn - xj);
+        acc += f[q] * (xn - x[nb[q]]);
     }
     *dg = d;
     return acc;
@@ -191,34 +191,36 @@ __device__ inline double sum_parts(const double* part, int nparts) {
     return res;
 }
 
-// First sweep from x = 0: x = omega D^-1 b. On the finest level this kernel
-// also finishes r.r of the CG update and tests convergence (flag `first`;
-// before the first iteration it also finishes b.b).
-__global__ __launch_bounds__(kBlock) void k_mg_first(MgArgs a, MgLevel L, int level, int first, int cg_blocks) {
+// Convergence test of the CG update (one block): finishes r.r (and b.b
+// before the first iteration) and sets done.
+__global__ void k_mg_test(MgArgs a, int cg_blocks) {
     DevState* s = a.s;
     if (s->done) return;
-    if (first) {
-        double rr = sum_parts(a.part_rr, cg_blocks);
-        double bb;
-        if (s->it == 0) {
-            bb = sum_parts(a.part_bb, cg_blocks);
-            if (blockIdx.x == 0 && threadIdx.x == 0) {
-                s->bb = bb;
-                s->rr0 = rr;
-            }
-        } else {
-            bb = s->bb;
+    double rr = sum_parts(a.part_rr, cg_blocks);
+    double bb;
+    if (s->it == 0) {
+        bb = sum_parts(a.part_bb, cg_blocks);
+        if (threadIdx.x == 0) {
+            s->bb = bb;
+            s->rr0 = rr;
         }
-        bool conv = (bb == 0.0) || (sqrt(rr) <= s->rtol * sqrt(bb)) || (s->it >= s->maxit);
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            s->rr = rr;
-            if (conv) {
-                s->done = 1;
-                s->zero_solution = (bb == 0.0);
-            }
-        }
-        if (conv) return;
+    } else {
+        bb = s->bb;
     }
+    bool conv = (bb == 0.0) || (sqrt(rr) <= s->rtol * sqrt(bb)) || (s->it >= s->maxit);
+    if (threadIdx.x == 0) {
+        s->rr = rr;
+        if (conv) {
+            s->done = 1;
+            s->zero_solution = (bb == 0.0);
+        }
+    }
+}
+
+// First sweep from x = 0: x = omega D^-1 b.
+__global__ __launch_bounds__(kBlock) void k_mg_first(MgArgs a, MgLevel L, int level) {
+    DevState* s = a.s;
+    if (s->done) return;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     NodeWalk wk((int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int)stride, L.nx, L.ny);
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < L.n; n += stride, wk.advance()) {
@@ -284,7 +286,9 @@ __global__ __launch_bounds__(kBlock) void k_mg_jacobi(MgArgs a, MgLevel L, int l
             for (int q = 0; q < 6; ++q) {
                 if (!has[q]) continue;
                 d += f[q];
-                double xj = a.type[nb[q]] == 0 ? val(nb[q], ni[q], nj[q], nk[q]) : 0.0;
+                // the coarse correction reaches free nodes only; without it the
+                // iterate is already zero on fixed nodes
+                double xj = xc ? (a.type[nb[q]] == 0 ? val(nb[q], ni[q], nj[q], nk[q]) : 0.0) : xi[nb[q]];
                 acc += f[q] * (xn - xj);
             }
             Ax = acc;
@@ -374,10 +378,11 @@ __global__ __launch_bounds__(1024) void k_mg_coarsest(MgArgs a, MgLevel L) {
 // ---------------------------------------------------------------------------
 // Host side
 
-static unsigned mg_grid(int64_t n, int level) {
-    if (level == 0) return kMgBlocks;  // as many partials as the CG kernels
+// One node per thread, except for the kernel that writes partial sums (a
+// fixed number of blocks, as many as the CG kernels read).
+static unsigned mg_grid(int64_t n, bool partials) {
+    if (partials) return kMgBlocks;
     int64_t g = (n + kBlock - 1) / kBlock;
-    if (g > kMgBlocks) g = kMgBlocks;
     return (unsigned)(g < 1 ? 1 : g);
 }
 
@@ -456,18 +461,18 @@ double* mg_vcycle(pic_ctx* c, double* part_rr, double* part_bb, double* part_rz,
     // descending: pre-smoothing and restriction
     for (int l = 0; l < nl - 1; ++l) {
         MgLevel& L = h->lv[l];
-        hipLaunchKernelGGL(k_mg_first, dim3(mg_grid(L.n, l)), dim3(kBlock), 0, c->stream, a, L, l, l == 0 ? 1 : 0,
-                           cg_blocks);
+        if (l == 0) hipLaunchKernelGGL(k_mg_test, dim3(1), dim3(kBlock), 0, c->stream, a, cg_blocks);
+        hipLaunchKernelGGL(k_mg_first, dim3(mg_grid(L.n, false)), dim3(kBlock), 0, c->stream, a, L, l);
         double* xi = L.x0;
         double* xo = L.x1;
         for (int s = 1; s < h->pre; ++s) {
-            hipLaunchKernelGGL(k_mg_jacobi, dim3(mg_grid(L.n, l)), dim3(kBlock), 0, c->stream, a, L, l, xi, xo,
+            hipLaunchKernelGGL(k_mg_jacobi, dim3(mg_grid(L.n, false)), dim3(kBlock), 0, c->stream, a, L, l, xi, xo,
                                (const double*)nullptr, h->lv[l + 1], 0.0, 0);
             std::swap(xi, xo);
         }
         // the pre-smoothed iterate must sit in x0 for the way up
         if (xi != L.x0) std::swap(L.x0, L.x1);
-        hipLaunchKernelGGL(k_mg_restrict, dim3(mg_grid(h->lv[l + 1].n, l + 1)), dim3(kBlock), 0, c->stream, a, L, l, L.x0,
+        hipLaunchKernelGGL(k_mg_restrict, dim3(mg_grid(h->lv[l + 1].n, false)), dim3(kBlock), 0, c->stream, a, L, l, L.x0,
                            h->lv[l + 1]);
     }
     hipLaunchKernelGGL(k_mg_coarsest, dim3(1), dim3(1024), 0, c->stream, a, h->lv[nl - 1]);
@@ -479,7 +484,7 @@ double* mg_vcycle(pic_ctx* c, double* part_rr, double* part_bb, double* part_rz,
         double* xo = L.x1;
         for (int s = 0; s < h->post; ++s) {
             bool last = (l == 0) && (s == h->post - 1);
-            hipLaunchKernelGGL(k_mg_jacobi, dim3(mg_grid(L.n, l)), dim3(kBlock), 0, c->stream, a, L, l, xi, xo,
+            hipLaunchKernelGGL(k_mg_jacobi, dim3(mg_grid(L.n, last)), dim3(kBlock), 0, c->stream, a, L, l, xi, xo,
                                s == 0 ? (const double*)h->lv[l + 1].x0 : (const double*)nullptr, h->lv[l + 1],
                                h->alpha_c, last ? 1 : 0);
             std::swap(xi, xo);

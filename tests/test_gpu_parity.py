@@ -315,3 +315,22 @@ def test_error_paths():
     g3 = pic.Simulation(cfg, caps=(1000, 100, 100), precision=F64)
     with pytest.raises(pic.PicError):
         g3.step(1, pic.STEP_COLLIDE)
+
+
+@pytest.mark.parametrize("precision", [F64, F32])
+def test_mgcg_solve_parity(precision):
+    """CG preconditioned by the multigrid V-cycle reaches the same potential
+    as the oracle's plain CG, in far fewer iterations."""
+    cfg = W.tiny()
+    load = W.initial_load(cfg, counts=(20000, 200, 0), seed=8)
+    g, o, _ = _pair(cfg, load, precision)
+    g.step(1, pic.STEP_DEPOSIT)
+    o.deposit()
+    info = g.solve(solver=pic.PIC_SOLVER_MGCG, guess=pic.PIC_GUESS_ZERO, rtol=1e-13)
+    it, rr = o.solve(rtol=1e-13, guess="zero")
+    assert info["converged"] and info["relres"] <= 1e-13
+    assert np.abs(g.grid("phi") - o.phi).max() <= 1e-10 * np.abs(o.phi).max()
+    assert info["iterations"] * 5 < it, (info["iterations"], it)
+    # the plain CG of the library from the same state agrees with both
+    info2 = g.solve(solver=pic.PIC_SOLVER_CG, guess=pic.PIC_GUESS_ZERO, rtol=1e-13)
+    assert np.abs(g.grid("phi") - o.phi).max() <= 1e-10 * np.abs(o.phi).max()
