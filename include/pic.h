@@ -65,6 +65,8 @@ typedef int32_t pic_status;
 /* initial guess of pic_solve_poisson */
 #define PIC_GUESS_ZERO 0
 #define PIC_GUESS_PREVIOUS 1
+#define PIC_GUESS_LAPLACE 2   /* V0 phi1: the exact charge-free solution */
+#define PIC_GUESS_LEARNED 3   /* V0 phi1 plus the network's charge response (pic_set_learned_guess) */
 
 /* phases of pic_step; each step runs the selected phases in this order */
 #define PIC_STEP_INJECT 0x01   /* Fowler-Nordheim emission from the tip (Sec. 2.3.1) */
@@ -237,6 +239,78 @@ pic_status pic_timers(pic_ctx* ctx, double* ms, int64_t* count, int32_t reset);
 
 const char* pic_last_error(const pic_ctx* ctx);
 void pic_destroy(pic_ctx* ctx);
+
+/* ---------------------------------------------------------------------------
+ * Learned warm start of the Poisson solve (an extension: the paper solves
+ * Eq. poi from the previous solution; here a network supplies the guess and
+ * CG to the same tolerance still decides the result, so a poor network costs
+ * iterations, never accuracy).
+ *
+ * Normalization. With q = rho 2^-40 (elementary charges per node) and
+ * s = max |q|, the network maps x = q / s to y, and the guess is
+ *   phi0 = V0 phi1 + (e s / (eps0 h)) y.
+ * The charge part phi_rho = phi - V0 phi1 solves A phi_rho = q e / (eps0 h)
+ * with zero on every fixed node, so y* = phi_rho eps0 h / (e s) solves A y* = x:
+ * the target is dimensionless and of order one whatever the charge.
+ *
+ * Network: a 3D U-Net on [batch][d][h][w] fp32 inputs (d = nz, h = ny,
+ * w = nx, each a multiple of 8): four levels of 16, 32, 64, 128 channels, two
+ * 3x3x3 convolutions with ReLU per level (zero padding), 2x2x2 stride-2
+ * convolutions with ReLU down, 2x2x2 stride-2 transposed convolutions up,
+ * skip connections by channel concatenation (upsampled first), and a linear
+ * 1x1x1 head. Weights and activations are bf16 on the matrix cores with fp32
+ * accumulation; the master parameters, gradients and Adam moments are fp32.
+ *
+ * Parameter vector (fp32, caller-owned device memory), layer by layer in
+ * network order, each as W then b: W[tap][cin][cout] with tap = 9 dz + 3 dy
+ * + dx (offsets -1..1) for the 3x3x3 convolutions and tap = 4 pz + 2 py + px
+ * (0..1) for the down convolutions (input voxel 2v + p) and the transposed
+ * convolutions (output voxel 2v + p); a concatenating layer takes the
+ * upsampled tensor as its first cin channels. The first layer reads 8 input
+ * channels of which only channel 0 carries x (the others are zero). The head
+ * is w[16] then b[1]. */
+typedef struct pic_unet_config {
+    int32_t base_channels; /* must be 16 */
+    int32_t reserved[7];
+} pic_unet_config;
+
+typedef struct unet unet;
+
+/* Number of fp32 parameters. */
+pic_status unet_param_count(const pic_unet_config* cfg, int64_t* n);
+/* Bytes of device work memory for a network over batch x d x h x w inputs. */
+pic_status unet_workspace_size(const pic_unet_config* cfg, int32_t batch, int32_t d, int32_t h, int32_t w,
+                               size_t* bytes);
+/* Create a network over caller-owned device memory: params and grads hold
+ * unet_param_count floats each, workspace (256-byte aligned) at least
+ * unet_workspace_size bytes. The parameters are read now and after every
+ * unet_adam_step / unet_sync_params. All work goes to hip_stream. */
+pic_status unet_create(const pic_unet_config* cfg, float* params, float* grads, void* workspace, size_t ws_bytes,
+                       int32_t batch, int32_t d, int32_t h, int32_t w, void* hip_stream, unet** out);
+/* y = net(x); x, y device fp32 [batch][d][h][w] (y may be NULL: the output
+ * stays inside the workspace for unet_backward). */
+pic_status unet_forward(unet* net, const float* x, float* y);
+/* Gradients of the mean squared error between the last forward output and
+ * target (device fp32, same shape) into grads (overwritten). loss (optional,
+ * host) receives the loss and makes the call synchronize. */
+pic_status unet_backward(unet* net, const float* target, double* loss);
+/* One Adam step (bias-corrected) on params with grads; refreshes the bf16
+ * weights. */
+pic_status unet_adam_step(unet* net, float lr, float beta1, float beta2, float eps);
+/* Re-read params after the caller changed them. */
+pic_status unet_sync_params(unet* net);
+void unet_destroy(unet* net);
+
+/* Use net (created with batch 1 over nz x ny x nx on the context's stream)
+ * for PIC_GUESS_LEARNED; NULL detaches. The network must outlive its use.
+ * smooth_passes (0..64) binomial [1 2 1]/4 filters along x, y and z are
+ * applied to the network output before it enters the guess. */
+pic_status pic_set_learned_guess(pic_ctx* ctx, unet* net, int32_t smooth_passes);
+/* A training pair from the current state: x = q / s from rho and
+ * y = (phi - V0 phi1) eps0 h / (e s) from phi (solve to a tight tolerance
+ * first). x, y: device fp32 [nz][ny][nx]; scale (optional, host) receives s
+ * (synchronizes). A state without charge gives x = y = 0 and s = 0. */
+pic_status pic_training_sample(pic_ctx* ctx, float* x, float* y, double* scale);
 
 #ifdef __cplusplus
 }

@@ -339,6 +339,11 @@ static pic_status solve(pic_ctx* c, int solver, int guess, double rtol, int maxi
     if (!info) info = &tmp;
     int th = tic(c, PIC_T_SOLVE);
     int r;
+    if (guess == PIC_GUESS_LAPLACE || guess == PIC_GUESS_LEARNED) {
+        r = guess_phi(c, guess == PIC_GUESS_LEARNED);
+        if (r != 0) return fail(c, PIC_E_HIP, "warm start failed");
+        guess = PIC_GUESS_PREVIOUS;
+    }
     if (solver == PIC_SOLVER_CG)
         r = cg_solve(c, c->buf.phi, c->V0, c->buf.rho, guess, rtol, maxit, info);
     else if (solver == PIC_SOLVER_MGCG)
@@ -401,7 +406,8 @@ pic_status pic_solve_poisson(pic_ctx* c, int32_t solver, int32_t guess, double r
                              pic_solve_info* info) {
     if (!c) return PIC_E_INVALID_ARG;
     if (c->failed) return PIC_E_STATE;
-    if (solver < PIC_SOLVER_CG || solver > PIC_SOLVER_MIXED || (guess != PIC_GUESS_ZERO && guess != PIC_GUESS_PREVIOUS) ||
+    if (solver < PIC_SOLVER_CG || solver > PIC_SOLVER_MIXED || guess < PIC_GUESS_ZERO || guess > PIC_GUESS_LEARNED ||
+        (guess == PIC_GUESS_LEARNED && !c->learned) ||
         !(rtol > 0) || maxit < 0)
         return fail(c, PIC_E_INVALID_ARG, "bad solver arguments");
     if (c->prof && c->ev_n > c->ev_max / 4) flush_timers(c);

@@ -49,6 +49,8 @@ struct DevState {
     unsigned int red_count;
     // mixed-precision refinement
     double rr_outer;
+    // learned warm start: s = max |q| of the current charge
+    double learn_scale;
 };
 
 // Cells are numbered tile-major: tiles of kTile^3 cells, tile index
@@ -282,6 +284,8 @@ struct pic_ctx {
     void* mg = nullptr;           // multigrid work memory
     void* mg_host = nullptr;      // multigrid hierarchy (host description)
     void* mixed = nullptr;        // mixed-precision vectors
+    struct unet* learned = nullptr;  // network of PIC_GUESS_LEARNED
+    int learn_smooth = 0;            // binomial filter passes on its output
     // host state
     pic::DevState* host_st = nullptr;  // pinned mirror
     int64_t step = 0;
@@ -325,6 +329,8 @@ hipError_t inject_phase(pic_ctx* c);
 hipError_t load_particles(pic_ctx* c, const pic_particles* src);
 hipError_t moments_phase(pic_ctx* c, double* out_dev);
 hipError_t apex_interp(pic_ctx* c, const double* phi, double X, double Y, double Z, double* out_dev);
+// phi = V0 phi1 (with_net = false) or V0 phi1 + network charge response
+int guess_phi(pic_ctx* c, bool with_net);
 // profiling: tic returns a handle for toc (or -1 when profiling is off)
 int tic(pic_ctx* c, int slot);
 void toc(pic_ctx* c, int h);

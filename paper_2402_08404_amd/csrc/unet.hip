@@ -1,0 +1,1037 @@
+// unet.hip -- the learned warm start: a 3D U-Net mapping the normalized node
+// charge to a potential guess, with forward, backward and Adam on the GPU.
+//
+// Convolutions are implicit GEMMs on the bf16 matrix cores
+// (v_mfma_f32_16x16x32_bf16, fp32 accumulation): rows are output voxels,
+// columns output channels, the reduction runs over (tap, input channel).
+// Activations are bf16, channels last ([voxel][channel]); master weights,
+// gradients and Adam moments are fp32. Gradients of activations are kept in
+// fp32 and rounded to bf16 (with the ReLU mask applied) where a GEMM reads them.
+//
+// Architecture (4 levels, 16-32-64-128 channels): two 3x3x3 conv + ReLU per
+// level, 2x2x2 stride-2 conv + ReLU down, 2x2x2 stride-2 transposed conv up,
+// skip connections by channel concatenation, 1x1x1 linear head.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pic_internal.hpp"
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned short bf16_t;  // storage type of one bf16
+
+namespace unet_impl {
+
+constexpr int kModeSame3 = 0, kModeDown2 = 1, kModeUp2 = 2;
+
+__device__ inline bf16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u) return (bf16_t)(u >> 16);  // inf / nan
+    u += 0x7FFFu + ((u >> 16) & 1u);                                  // round to nearest even
+    return (bf16_t)(u >> 16);
+}
+__device__ inline float bf2f(bf16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+
+struct Geo {
+    int B, D, H, W;  // grid of the GEMM rows (output voxels, or coarse voxels for up)
+    int iD, iH, iW;  // grid of the input tensor(s)
+};
+
+// ---------------------------------------------------------------------------
+// Forward-type convolution (also used for input gradients).
+// out[v][co] = act(bias[co] + sum_k A(v, k) W[co][k]),  k = tap * Cin + ci.
+// mode Same3: 27 taps, input voxel v + offset(tap) (zero outside the sample);
+//   flip: tap t reads offset(26 - t) (transposed stencil for input gradients).
+// mode Down2: 8 taps, input voxel 2 v + offset(tap) on the finer input grid.
+// mode Up2: rows are coarse voxels vc, one tap, output voxel 2 vc + par.
+struct ConvArgs {
+    const bf16_t* a;    // input A, channels ca
+    const bf16_t* b;    // input B (concatenated after A), channels cb
+    const bf16_t* w;    // [N][Kpad]
+    const float* bias;  // [N] or null
+    bf16_t* out;        // bf16 output [vox][N] or null
+    float* out32;       // fp32 output [vox][N] or null
+    int accumulate;     // out32 += result
+    int ca, cb, N, K, Kpad, mode, relu, flip, par;
+    Geo g;
+};
+
+__device__ inline int src_voxel(const ConvArgs& p, int64_t v, int tap, bool& ok) {
+    const Geo& g = p.g;
+    int x = (int)(v % g.W);
+    int64_t r = v / g.W;
+    int y = (int)(r % g.H);
+    r /= g.H;
+    int z = (int)(r % g.D);
+    int bsm = (int)(r / g.D);
+    int sx, sy, sz;
+    if (p.mode == kModeSame3) {
+        int t = p.flip ? 26 - tap : tap;
+        sx = x + (t % 3) - 1;
+        sy = y + ((t / 3) % 3) - 1;
+        sz = z + (t / 9) - 1;
+    } else if (p.mode == kModeDown2) {
+        sx = 2 * x + (tap & 1);
+        sy = 2 * y + ((tap >> 1) & 1);
+        sz = 2 * z + ((tap >> 2) & 1);
+    } else {
+        sx = x;
+        sy = y;
+        sz = z;
+    }
+    ok = sx >= 0 && sx < g.iW && sy >= 0 && sy < g.iH && sz >= 0 && sz < g.iD;
+    return (int)((((int64_t)bsm * g.iD + sz) * g.iH + sy) * g.iW + sx);
+}
+
+__device__ inline int64_t out_voxel(const ConvArgs& p, int64_t v) {
+    if (p.mode != kModeUp2) return v;
+    const Geo& g = p.g;
+    int x = (int)(v % g.W);
+    int64_t r = v / g.W;
+    int y = (int)(r % g.H);
+    r /= g.H;
+    int z = (int)(r % g.D);
+    int bsm = (int)(r / g.D);
+    int X = 2 * x + (p.par & 1), Y = 2 * y + ((p.par >> 1) & 1), Z = 2 * z + ((p.par >> 2) & 1);
+    return (((int64_t)bsm * (2 * g.D) + Z) * (2 * g.H) + Y) * (2 * g.W) + X;
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_conv(ConvArgs p) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t M = (int64_t)p.g.B * p.g.D * p.g.H * p.g.W;
+    const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
+    const int64_t v = row0 + (lane & 15);
+    const bool vrow = v < M;
+    const int cin = p.ca + p.cb;
+    f32x4 acc[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const int kg = 8 * (lane >> 4);
+    for (int kc = 0; kc < p.Kpad; kc += 32) {
+        int k0 = kc + kg;
+        bf16x8 av;
+        uint4 raw = make_uint4(0, 0, 0, 0);
+        if (vrow && k0 < p.K) {
+            int tap = k0 / cin, ci = k0 - tap * cin;
+            bool ok;
+            int s = src_voxel(p, v, tap, ok);
+            if (ok) {
+                const bf16_t* src = ci < p.ca ? p.a + (int64_t)s * p.ca + ci : p.b + (int64_t)s * p.cb + (ci - p.ca);
+                raw = *(const uint4*)src;
+            }
+        }
+        av = *(bf16x8*)&raw;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const bf16_t* wp = p.w + (int64_t)(nb * 16 + (lane & 15)) * p.Kpad + k0;
+            uint4 wr = *(const uint4*)wp;
+            bf16x8 bv = *(bf16x8*)&wr;
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[nb], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        int co = nb * 16 + (lane & 15);
+        float bias = p.bias ? p.bias[co] : 0.f;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int64_t r = row0 + 4 * (lane >> 4) + j;
+            if (r >= M) continue;
+            float val = acc[nb][j] + bias;
+            if (p.relu) val = val > 0.f ? val : 0.f;
+            int64_t o = out_voxel(p, r);
+            if (p.out) p.out[o * p.N + co] = f2bf(val);
+            if (p.out32) {
+                float* q = p.out32 + o * p.N + co;
+                *q = p.accumulate ? *q + val : val;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: dW[tap][ci][co] = sum_v A(v, tap)[ci] G[v][co] over the
+// GEMM rows v of the forward layer; split over row ranges, partials written
+// per split and summed in a fixed order afterwards.
+struct WgradArgs {
+    const bf16_t* a;
+    const bf16_t* b;
+    const bf16_t* gr;   // G [rows][N] (output-voxel order of the forward)
+    float* part;        // [nsplit][taps][cin][N]
+    int ca, cb, N, taps, mode, par;
+    int64_t rows_per_split;
+    Geo g;
+};
+
+template <int MB, int NBW>
+__global__ __launch_bounds__(256) void k_wgrad(WgradArgs p) {
+    // block: one tap and one split; 4 waves share the (cin x N) tiles
+    __shared__ __align__(16) bf16_t As[32][128 + 8];
+    __shared__ __align__(16) bf16_t Gs[32][128 + 8];
+    const int tap = blockIdx.x % p.taps;
+    const int split = blockIdx.x / p.taps;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cin = p.ca + p.cb;
+    const int64_t M = (int64_t)p.g.B * p.g.D * p.g.H * p.g.W;
+    int64_t r0 = (int64_t)split * p.rows_per_split, r1 = r0 + p.rows_per_split;
+    if (r1 > M) r1 = M;
+    const int cin16 = (cin + 15) / 16 * 16;  // the 8-channel input is padded with zero columns
+    const int mt = cin16 / 16, nt = p.N / 16;
+    const int ntile = mt * nt;
+    f32x4 acc[MB * NBW];
+#pragma unroll
+    for (int q = 0; q < MB * NBW; ++q) acc[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    ConvArgs cp;
+    cp.mode = p.mode;
+    cp.flip = 0;
+    cp.par = p.par;
+    cp.g = p.g;
+    for (int64_t rb = r0; rb < r1; rb += 32) {
+        // stage 32 rows of A (the tap's input voxels) and of G
+        for (int e = threadIdx.x; e < 32 * (cin16 / 8); e += blockDim.x) {
+            int rr = e / (cin16 / 8), c8 = (e % (cin16 / 8)) * 8;
+            int64_t v = rb + rr;
+            uint4 raw = make_uint4(0, 0, 0, 0);
+            if (v < r1 && c8 < cin) {
+                bool ok = true;
+                int s = src_voxel(cp, v, tap, ok);
+                if (ok) raw = c8 < p.ca ? *(const uint4*)(p.a + (int64_t)s * p.ca + c8)
+                                        : *(const uint4*)(p.b + (int64_t)s * p.cb + (c8 - p.ca));
+            }
+            *(uint4*)&As[rr][c8] = raw;
+        }
+        for (int e = threadIdx.x; e < 32 * (p.N / 8); e += blockDim.x) {
+            int rr = e / (p.N / 8), c8 = (e % (p.N / 8)) * 8;
+            int64_t v = rb + rr;
+            uint4 raw = make_uint4(0, 0, 0, 0);
+            if (v < r1) {
+                int64_t o = out_voxel(cp, v);
+                raw = *(const uint4*)(p.gr + o * p.N + c8);
+            }
+            *(uint4*)&Gs[rr][c8] = raw;
+        }
+        __syncthreads();
+        // C[ci][co] += A^T[ci][row] G[row][co]: K = 32 rows
+        const int kg = 8 * (lane >> 4);
+#pragma unroll
+        for (int q = 0; q < MB * NBW; ++q) {
+            int tile = wave + 4 * q;
+            if (tile < ntile) {
+                int mb = tile / nt, nb = tile % nt;
+                bf16x8 av, bv;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    bf16_t x = As[kg + j][mb * 16 + (lane & 15)];
+                    bf16_t y = Gs[kg + j][nb * 16 + (lane & 15)];
+                    av[j] = *(__bf16*)&x;
+                    bv[j] = *(__bf16*)&y;
+                }
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[q], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < MB * NBW; ++q) {
+        int tile = wave + 4 * q;
+        if (tile < ntile) {
+            int mb = tile / nt, nb = tile % nt;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                int ci = mb * 16 + 4 * (lane >> 4) + j, co = nb * 16 + (lane & 15);
+                if (ci < cin) p.part[(((int64_t)split * p.taps + tap) * cin + ci) * p.N + co] = acc[q][j];
+            }
+        }
+    }
+}
+
+// gW[i] = sum over splits of part[s][i] (fixed order)
+__global__ void k_sum_splits(const float* part, int nsplit, int64_t n, float* gw) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * n + i];
+    gw[i] = s;
+}
+
+// gb[co] = sum over voxels of G[v][co]: per-block partial sums then a final
+// pass in a fixed order.
+__global__ void k_bias_partial(const float* g32, int64_t M, int N, float* part) {
+    int co = threadIdx.x % N;
+    int lanes = blockDim.x / N;
+    int sub = threadIdx.x / N;
+    float s = 0.f;
+    int64_t per = (M + gridDim.x - 1) / gridDim.x;
+    int64_t v0 = (int64_t)blockIdx.x * per, v1 = v0 + per < M ? v0 + per : M;
+    for (int64_t v = v0 + sub; v < v1; v += lanes) s += g32[v * N + co];
+    __shared__ float sh[256];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    if (sub == 0) {
+        float t = 0.f;
+        for (int q = 0; q < lanes; ++q) t += sh[q * N + co];
+        part[(int64_t)blockIdx.x * N + co] = t;
+    }
+}
+
+// G (bf16) = g32 * (y > 0) for a ReLU layer, or g32 for a linear one; the
+// fp32 gradient after the mask is kept for the bias gradient.
+__global__ void k_mask(const float* g32, const bf16_t* y, int relu, int64_t n, bf16_t* G, float* gm32) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float v = g32[i];
+    if (relu && !(bf2f(y[i]) > 0.f)) v = 0.f;
+    G[i] = f2bf(v);
+    gm32[i] = v;
+}
+
+// Input: normalized charge (fp32 [vox]) into a bf16 tensor of 8 channels.
+__global__ void k_input(const float* x, int64_t n, bf16_t* t) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint4 z = make_uint4(0, 0, 0, 0);
+    *(uint4*)(t + i * 8) = z;
+    t[i * 8] = f2bf(x[i]);
+}
+
+// Head: out[v] = sum_ci y[v][ci] w[ci] + b (fp32).
+__global__ void k_head(const bf16_t* y, int C, const float* w, const float* b, int64_t n, float* out) {
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    float s = b[0];
+    for (int c = 0; c < C; ++c) s += bf2f(y[v * C + c]) * w[c];
+    out[v] = s;
+}
+
+// MSE loss: dout = 2 (out - target) / n; per-block partial sums of the
+// squared error.
+__global__ void k_mse(const float* out, const float* target, int64_t n, float* dout, float* part) {
+    __shared__ float sh[4];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float e = 0.f;
+    if (i < n) {
+        float d = out[i] - target[i];
+        dout[i] = 2.f * d / (float)n;
+        e = d * d;
+    }
+    float t = pic::block_sum(e, sh);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+// Head backward: dy[v][c] = dout[v] w[c]; partials of dw[c] = sum dout y and db.
+__global__ void k_head_back(const bf16_t* y, int C, const float* w, const float* dout, int64_t n, float* dy,
+                            float* part) {
+    __shared__ float sh[4];
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float d = v < n ? dout[v] : 0.f;
+    for (int c = 0; c < C; ++c) {
+        float yc = v < n ? bf2f(y[v * C + c]) : 0.f;
+        if (v < n) dy[v * C + c] = d * w[c];
+        float t = pic::block_sum(d * yc, sh);
+        if (threadIdx.x == 0) part[(int64_t)blockIdx.x * (C + 1) + c] = t;
+    }
+    float t = pic::block_sum(d, sh);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.x * (C + 1) + C] = t;
+}
+
+__global__ void k_sum_cols(const float* part, int nrows, int ncols, float* out) {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ncols) return;
+    float s = 0.f;
+    for (int r = 0; r < nrows; ++r) s += part[(int64_t)r * ncols + c];
+    out[c] = s;
+}
+
+// Adam (fp32 master weights).
+__global__ void k_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float gi = g[i];
+    float mi = b1 * m[i] + (1.f - b1) * gi;
+    float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// bf16 weight copies from the fp32 master W[tap][ci][co].
+// Forward B operand: Wf[co][k], k = tap * cin + ci (sliced: one [co][ci]
+// block per tap, for the up convolution whose rows each use one tap).
+// Input-gradient B operand: Wb[ci][k], k = tap * cout + co (sliced: one
+// [ci][co] block per tap, for the down convolution). Rows padded to Kf / Kb.
+__global__ void k_pack_w(const float* w, int taps, int cin, int cout, int Kf, int sf, int Kb, int sb, bf16_t* wf,
+                         bf16_t* wb) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t nf = (int64_t)(sf ? taps : 1) * cout * Kf, nb = (int64_t)(sb ? taps : 1) * cin * Kb;
+    if (i < nf) {
+        float val = 0.f;
+        if (sf) {
+            int t = (int)(i / ((int64_t)cout * Kf));
+            int64_t r = i % ((int64_t)cout * Kf);
+            int co = (int)(r / Kf), ci = (int)(r % Kf);
+            if (ci < cin) val = w[((int64_t)t * cin + ci) * cout + co];
+        } else {
+            int co = (int)(i / Kf), k = (int)(i % Kf);
+            if (k < taps * cin) val = w[((int64_t)(k / cin) * cin + (k % cin)) * cout + co];
+        }
+        wf[i] = f2bf(val);
+    }
+    if (i < nb) {
+        float val = 0.f;
+        if (sb) {
+            int t = (int)(i / ((int64_t)cin * Kb));
+            int64_t r = i % ((int64_t)cin * Kb);
+            int ci = (int)(r / Kb), co = (int)(r % Kb);
+            if (co < cout) val = w[((int64_t)t * cin + ci) * cout + co];
+        } else {
+            int ci = (int)(i / Kb), k = (int)(i % Kb);
+            if (k < taps * cout) val = w[((int64_t)(k / cout) * cin + ci) * cout + (k % cout)];
+        }
+        wb[i] = f2bf(val);
+    }
+}
+
+// g_a[v][0..ca) += t[v][0..ca), g_b[v][0..cb) += t[v][ca..ca+cb)
+__global__ void k_split_add(const float* t, int64_t nvox, int ca, int cb, float* ga, float* gb) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int c = ca + cb;
+    if (i >= nvox * c) return;
+    int64_t v = i / c;
+    int ch = (int)(i % c);
+    if (ch < ca) ga[v * ca + ch] += t[i];
+    else gb[v * cb + (ch - ca)] += t[i];
+}
+
+__global__ void k_copy_f32(const float* a, float* b, int64_t n, float scale) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = a[i] * scale;
+}
+
+}  // namespace unet_impl
+
+// ---------------------------------------------------------------------------
+// Host side
+
+using namespace unet_impl;
+
+struct UnetLayer {
+    int mode, ca, cb, cout, taps, relu;
+    int64_t w_off, b_off;     // into the parameter vector
+    int Kf, Kb;
+    bf16_t *wf, *wb;          // bf16 copies
+    int in_a, in_b, out;      // activation tensor indices (-1 none)
+    Geo g;                    // GEMM row grid and input grid
+};
+
+struct unet {
+    pic_unet_config cfg;
+    hipStream_t stream;
+    int B, D, H, W;
+    float* params;
+    float* grads;
+    float *adam_m, *adam_v;
+    int64_t nparams;
+    int64_t adam_t;
+    std::vector<UnetLayer> L;
+    // activation tensors: bf16 values, fp32 gradients
+    std::vector<bf16_t*> act;
+    std::vector<float*> gact;
+    std::vector<int> act_c;
+    std::vector<int64_t> act_n;   // voxels
+    int in_t, head_in;
+    int64_t head_w, head_b;
+    float *out, *dout;
+    bf16_t* G;                    // masked gradient (bf16) scratch
+    float* gm32;                  // masked gradient (fp32) scratch
+    float* tmp32;                 // input gradient of a concatenating layer before the split
+    float* part;                  // partial sums
+    int64_t part_n;
+    float* loss_part;
+    char* ws;
+    size_t ws_bytes, ws_used;
+    std::string err;
+};
+
+static char* ws_take(unet* u, size_t bytes) {
+    size_t off = (u->ws_used + 255) & ~size_t(255);
+    if (off + bytes > u->ws_bytes) return nullptr;
+    u->ws_used = off + bytes;
+    return u->ws + off;
+}
+
+struct Plan {
+    std::vector<UnetLayer> L;
+    std::vector<int> act_c;
+    std::vector<int64_t> act_n;
+    int64_t nparams = 0;
+    int head_in = -1, in_t = 0;
+    int64_t head_w = 0, head_b = 0;
+};
+
+static Plan make_plan(const pic_unet_config* c, int B, int D, int H, int W) {
+    Plan p;
+    int ch[4] = {c->base_channels, 2 * c->base_channels, 4 * c->base_channels, 8 * c->base_channels};
+    auto tensor = [&](int C, int64_t vox) {
+        p.act_c.push_back(C);
+        p.act_n.push_back(vox);
+        return (int)p.act_c.size() - 1;
+    };
+    int64_t vox[4];
+    int dims[4][3];
+    for (int l = 0; l < 4; ++l) {
+        dims[l][0] = D >> l;
+        dims[l][1] = H >> l;
+        dims[l][2] = W >> l;
+        vox[l] = (int64_t)B * dims[l][0] * dims[l][1] * dims[l][2];
+    }
+    auto geo = [&](int lo, int li) {
+        Geo g;
+        g.B = B;
+        g.D = dims[lo][0];
+        g.H = dims[lo][1];
+        g.W = dims[lo][2];
+        g.iD = dims[li][0];
+        g.iH = dims[li][1];
+        g.iW = dims[li][2];
+        return g;
+    };
+    auto add = [&](int mode, int a, int b, int cout, int relu, int lo, int li) {
+        UnetLayer y;
+        y.mode = mode;
+        y.ca = p.act_c[a];
+        y.cb = b >= 0 ? p.act_c[b] : 0;
+        y.cout = cout;
+        y.taps = mode == kModeSame3 ? 27 : 8;
+        y.relu = relu;
+        y.in_a = a;
+        y.in_b = b;
+        y.w_off = p.nparams;
+        p.nparams += (int64_t)y.taps * (y.ca + y.cb) * cout;
+        y.b_off = p.nparams;
+        p.nparams += cout;
+        int cin = y.ca + y.cb;
+        y.Kf = (mode == kModeUp2 ? cin : y.taps * cin);      // per slice for the up convolution
+        y.Kf = (y.Kf + 31) / 32 * 32;
+        y.Kb = (mode == kModeDown2 ? cout : y.taps * cout);  // per slice for the down convolution
+        y.Kb = (y.Kb + 31) / 32 * 32;
+        int lo_t = mode == kModeUp2 ? li : lo;  // GEMM rows of the up conv are coarse voxels
+        y.g = geo(lo_t, li);
+        y.out = tensor(cout, vox[lo]);
+        p.L.push_back(y);
+        return y.out;
+    };
+    p.in_t = tensor(8, vox[0]);
+    int x = add(kModeSame3, p.in_t, -1, ch[0], 1, 0, 0);
+    int s0 = add(kModeSame3, x, -1, ch[0], 1, 0, 0);
+    x = add(kModeDown2, s0, -1, ch[1], 1, 1, 0);
+    x = add(kModeSame3, x, -1, ch[1], 1, 1, 1);
+    int s1 = add(kModeSame3, x, -1, ch[1], 1, 1, 1);
+    x = add(kModeDown2, s1, -1, ch[2], 1, 2, 1);
+    x = add(kModeSame3, x, -1, ch[2], 1, 2, 2);
+    int s2 = add(kModeSame3, x, -1, ch[2], 1, 2, 2);
+    x = add(kModeDown2, s2, -1, ch[3], 1, 3, 2);
+    x = add(kModeSame3, x, -1, ch[3], 1, 3, 3);
+    x = add(kModeSame3, x, -1, ch[3], 1, 3, 3);
+    x = add(kModeUp2, x, -1, ch[2], 0, 2, 3);
+    x = add(kModeSame3, x, s2, ch[2], 1, 2, 2);
+    x = add(kModeSame3, x, -1, ch[2], 1, 2, 2);
+    x = add(kModeUp2, x, -1, ch[1], 0, 1, 2);
+    x = add(kModeSame3, x, s1, ch[1], 1, 1, 1);
+    x = add(kModeSame3, x, -1, ch[1], 1, 1, 1);
+    x = add(kModeUp2, x, -1, ch[0], 0, 0, 1);
+    x = add(kModeSame3, x, s0, ch[0], 1, 0, 0);
+    x = add(kModeSame3, x, -1, ch[0], 1, 0, 0);
+    p.head_in = x;
+    p.head_w = p.nparams;
+    p.nparams += ch[0];
+    p.head_b = p.nparams;
+    p.nparams += 1;
+    return p;
+}
+
+static int64_t wgrad_splits(int64_t M) {
+    int64_t s = (M + 4095) / 4096;
+    return s < 1 ? 1 : (s > 256 ? 256 : s);
+}
+
+static size_t plan_bytes(const Plan& p, int64_t vox0) {
+    size_t b = 0;
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    for (size_t i = 0; i < p.act_c.size(); ++i) {
+        b += al((size_t)p.act_n[i] * p.act_c[i] * 2);
+        b += al((size_t)p.act_n[i] * p.act_c[i] * 4);
+    }
+    int64_t maxe = 0, maxpart = 0;
+    for (const UnetLayer& y : p.L) {
+        b += al((size_t)(y.mode == kModeUp2 ? 8 : 1) * y.cout * y.Kf * 2) +
+             al((size_t)(y.mode == kModeDown2 ? 8 : 1) * (y.ca + y.cb) * y.Kb * 2);
+        int64_t rows = (int64_t)y.g.B * y.g.D * y.g.H * y.g.W;
+        maxe = std::max<int64_t>(maxe, (y.mode == kModeUp2 ? 8 * rows : rows) * std::max(y.cout, y.ca + y.cb));
+        int64_t taps = y.mode == kModeUp2 ? 8 : y.taps;
+        maxpart = std::max<int64_t>(maxpart, wgrad_splits(rows) * taps * (y.ca + y.cb) * y.cout);
+    }
+    maxpart = std::max<int64_t>(maxpart, ((vox0 + 255) / 256) * 64);
+    b += al(maxe * 2) + 2 * al(maxe * 4) + al(maxpart * 4) + 2 * al(p.nparams * 4) + 2 * al(vox0 * 4) +
+         al(((vox0 + 255) / 256 + 1) * 4) + 4096;
+    return b;
+}
+
+static unsigned nblk(int64_t n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+static void launch_conv(unet* u, const UnetLayer& y, const bf16_t* a, const bf16_t* b, const bf16_t* w, int ca, int cb,
+                        int N, int K, int Kpad, int mode, int relu, int flip, int par, Geo g, const float* bias,
+                        bf16_t* out, float* out32, int accumulate) {
+    ConvArgs p;
+    p.a = a;
+    p.b = b;
+    p.w = w;
+    p.bias = bias;
+    p.out = out;
+    p.out32 = out32;
+    p.accumulate = accumulate;
+    p.ca = ca;
+    p.cb = cb;
+    p.N = N;
+    p.K = K;
+    p.Kpad = Kpad;
+    p.mode = mode;
+    p.relu = relu;
+    p.flip = flip;
+    p.par = par;
+    p.g = g;
+    int64_t M = (int64_t)g.B * g.D * g.H * g.W;
+    unsigned G = nblk(M, 64);
+    switch (N / 16) {
+        case 1: hipLaunchKernelGGL(k_conv<1>, dim3(G), dim3(256), 0, u->stream, p); break;
+        case 2: hipLaunchKernelGGL(k_conv<2>, dim3(G), dim3(256), 0, u->stream, p); break;
+        case 4: hipLaunchKernelGGL(k_conv<4>, dim3(G), dim3(256), 0, u->stream, p); break;
+        case 8: hipLaunchKernelGGL(k_conv<8>, dim3(G), dim3(256), 0, u->stream, p); break;
+        default: u->err = "unsupported channel count"; break;
+    }
+    (void)y;
+}
+
+static void pack_weights(unet* u) {
+    for (UnetLayer& y : u->L) {
+        int cin = y.ca + y.cb;
+        int sf = y.mode == kModeUp2, sb = y.mode == kModeDown2;
+        int64_t n = std::max<int64_t>((int64_t)(sf ? 8 : 1) * y.cout * y.Kf, (int64_t)(sb ? 8 : 1) * cin * y.Kb);
+        hipLaunchKernelGGL(k_pack_w, dim3(nblk(n)), dim3(256), 0, u->stream, u->params + y.w_off, y.taps, cin, y.cout,
+                           y.Kf, sf, y.Kb, sb, y.wf, y.wb);
+    }
+}
+
+extern "C" {
+
+pic_status unet_param_count(const pic_unet_config* c, int64_t* n) {
+    if (!c || !n || c->base_channels < 16 || c->base_channels % 16 != 0 || c->base_channels > 16) return PIC_E_INVALID_ARG;
+    Plan p = make_plan(c, 1, 8, 8, 8);
+    *n = p.nparams;
+    return PIC_OK;
+}
+
+pic_status unet_workspace_size(const pic_unet_config* c, int batch, int d, int h, int w, size_t* bytes) {
+    if (!c || !bytes || batch < 1 || d < 8 || h < 8 || w < 8 || d % 8 || h % 8 || w % 8) return PIC_E_INVALID_ARG;
+    if (c->base_channels != 16) return PIC_E_INVALID_ARG;
+    Plan p = make_plan(c, batch, d, h, w);
+    *bytes = plan_bytes(p, (int64_t)batch * d * h * w);
+    return PIC_OK;
+}
+
+pic_status unet_create(const pic_unet_config* c, float* params, float* grads, void* workspace, size_t ws_bytes,
+                       int batch, int d, int h, int w, void* stream, unet** out) {
+    if (!out) return PIC_E_INVALID_ARG;
+    *out = nullptr;
+    size_t need = 0;
+    if (unet_workspace_size(c, batch, d, h, w, &need) != PIC_OK || !params || !grads || !workspace || ws_bytes < need ||
+        ((uintptr_t)workspace) % 256)
+        return PIC_E_INVALID_ARG;
+    unet* u = new unet();
+    u->cfg = *c;
+    u->stream = (hipStream_t)stream;
+    u->B = batch;
+    u->D = d;
+    u->H = h;
+    u->W = w;
+    u->params = params;
+    u->grads = grads;
+    u->ws = (char*)workspace;
+    u->ws_bytes = ws_bytes;
+    u->ws_used = 0;
+    Plan p = make_plan(c, batch, d, h, w);
+    u->L = p.L;
+    u->act_c = p.act_c;
+    u->act_n = p.act_n;
+    u->nparams = p.nparams;
+    u->head_in = p.head_in;
+    u->in_t = p.in_t;
+    u->head_w = p.head_w;
+    u->head_b = p.head_b;
+    for (size_t i = 0; i < p.act_c.size(); ++i) {
+        u->act.push_back((bf16_t*)ws_take(u, (size_t)p.act_n[i] * p.act_c[i] * 2));
+        u->gact.push_back((float*)ws_take(u, (size_t)p.act_n[i] * p.act_c[i] * 4));
+    }
+    int64_t maxe = 0, maxpart = 0;
+    for (UnetLayer& y : u->L) {
+        y.wf = (bf16_t*)ws_take(u, (size_t)(y.mode == kModeUp2 ? 8 : 1) * y.cout * y.Kf * 2);
+        y.wb = (bf16_t*)ws_take(u, (size_t)(y.mode == kModeDown2 ? 8 : 1) * (y.ca + y.cb) * y.Kb * 2);
+        int64_t rows = (int64_t)y.g.B * y.g.D * y.g.H * y.g.W;
+        maxe = std::max<int64_t>(maxe, (y.mode == kModeUp2 ? 8 * rows : rows) * std::max(y.cout, y.ca + y.cb));
+        int64_t taps = y.mode == kModeUp2 ? 8 : y.taps;
+        maxpart = std::max<int64_t>(maxpart, wgrad_splits(rows) * taps * (y.ca + y.cb) * y.cout);
+    }
+    int64_t vox0 = (int64_t)batch * d * h * w;
+    maxpart = std::max<int64_t>(maxpart, ((vox0 + 255) / 256) * 64);
+    u->G = (bf16_t*)ws_take(u, maxe * 2);
+    u->gm32 = (float*)ws_take(u, maxe * 4);
+    u->tmp32 = (float*)ws_take(u, maxe * 4);
+    u->part = (float*)ws_take(u, maxpart * 4);
+    u->part_n = maxpart;
+    u->adam_m = (float*)ws_take(u, u->nparams * 4);
+    u->adam_v = (float*)ws_take(u, u->nparams * 4);
+    u->out = (float*)ws_take(u, vox0 * 4);
+    u->dout = (float*)ws_take(u, vox0 * 4);
+    u->loss_part = (float*)ws_take(u, ((vox0 + 255) / 256 + 1) * 4);
+    if (!u->loss_part) {
+        delete u;
+        return PIC_E_INVALID_ARG;
+    }
+    (void)pic::launch_zero(u->adam_m, u->nparams * 4, u->stream);
+    (void)pic::launch_zero(u->adam_v, u->nparams * 4, u->stream);
+    u->adam_t = 0;
+    pack_weights(u);
+    if (hipGetLastError() != hipSuccess) {
+        delete u;
+        return PIC_E_HIP;
+    }
+    *out = u;
+    return PIC_OK;
+}
+
+// Forward: x (fp32, [batch][d][h][w]) -> y (fp32, same shape). The weights
+// are read from the parameter vector as last packed (unet_create,
+// unet_adam_step, unet_sync_params).
+pic_status unet_forward(unet* u, const float* x, float* y) {
+    if (!u || !x) return PIC_E_INVALID_ARG;
+    int64_t n0 = u->act_n[u->in_t];
+    hipLaunchKernelGGL(k_input, dim3(nblk(n0)), dim3(256), 0, u->stream, x, n0, u->act[u->in_t]);
+    for (const UnetLayer& l : u->L) {
+        const bf16_t* a = u->act[l.in_a];
+        const bf16_t* b = l.in_b >= 0 ? u->act[l.in_b] : nullptr;
+        int cin = l.ca + l.cb;
+        const float* bias = u->params + l.b_off;
+        if (l.mode == kModeUp2) {
+            for (int par = 0; par < 8; ++par)
+                launch_conv(u, l, a, b, l.wf + (int64_t)par * l.cout * l.Kf, l.ca, l.cb, l.cout, cin, l.Kf, kModeUp2,
+                            l.relu, 0, par, l.g, bias, u->act[l.out], nullptr, 0);
+        } else {
+            launch_conv(u, l, a, b, l.wf, l.ca, l.cb, l.cout, l.taps * cin, l.Kf, l.mode, l.relu, 0, 0, l.g, bias,
+                        u->act[l.out], nullptr, 0);
+        }
+    }
+    hipLaunchKernelGGL(k_head, dim3(nblk(n0)), dim3(256), 0, u->stream, u->act[u->head_in], u->act_c[u->head_in],
+                       u->params + u->head_w, u->params + u->head_b, n0, u->out);
+    if (y) hipLaunchKernelGGL(k_copy_f32, dim3(nblk(n0)), dim3(256), 0, u->stream, u->out, y, n0, 1.0f);
+    return hipGetLastError() == hipSuccess && u->err.empty() ? PIC_OK : PIC_E_HIP;
+}
+
+}  // extern "C"
+
+static void launch_wgrad(unet* u, const UnetLayer& l, const bf16_t* a, const bf16_t* b, int taps, int par, Geo g,
+                         float* dst) {
+    WgradArgs w;
+    w.a = a;
+    w.b = b;
+    w.gr = u->G;
+    w.part = u->part;
+    w.ca = l.ca;
+    w.cb = l.cb;
+    w.N = l.cout;
+    w.taps = taps;
+    w.mode = l.mode;
+    w.par = par;
+    w.g = g;
+    int64_t rows = (int64_t)g.B * g.D * g.H * g.W;
+    int64_t ns = wgrad_splits(rows);
+    w.rows_per_split = (rows + ns - 1) / ns;
+    hipLaunchKernelGGL((k_wgrad<4, 4>), dim3((unsigned)(ns * taps)), dim3(256), 0, u->stream, w);
+    int64_t n = (int64_t)taps * (l.ca + l.cb) * l.cout;
+    hipLaunchKernelGGL(k_sum_splits, dim3(nblk(n)), dim3(256), 0, u->stream, (const float*)u->part, (int)ns, n, dst);
+}
+
+extern "C" {
+
+// Backward of the last forward against target (fp32, same shape as the
+// output): MSE loss, gradients of every parameter into the gradient vector.
+// loss (host, optional) receives the mean squared error (synchronizes).
+pic_status unet_backward(unet* u, const float* target, double* loss) {
+    if (!u || !target) return PIC_E_INVALID_ARG;
+    int64_t n0 = u->act_n[u->in_t];
+    unsigned nb0 = nblk(n0);
+    hipLaunchKernelGGL(k_mse, dim3(nb0), dim3(256), 0, u->stream, (const float*)u->out, target, n0, u->dout,
+                       u->loss_part);
+    for (size_t i = 0; i < u->act.size(); ++i)
+        (void)pic::launch_zero(u->gact[i], (size_t)u->act_n[i] * u->act_c[i] * 4, u->stream);
+    int Ch = u->act_c[u->head_in];
+    hipLaunchKernelGGL(k_head_back, dim3(nb0), dim3(256), 0, u->stream, (const bf16_t*)u->act[u->head_in], Ch,
+                       (const float*)(u->params + u->head_w), (const float*)u->dout, n0, u->gact[u->head_in], u->part);
+    hipLaunchKernelGGL(k_sum_cols, dim3(1), dim3(256), 0, u->stream, (const float*)u->part, (int)nb0, Ch + 1,
+                       u->grads + u->head_w);  // head_b follows head_w
+    for (int li = (int)u->L.size() - 1; li >= 0; --li) {
+        const UnetLayer& l = u->L[li];
+        int64_t nout = u->act_n[l.out] * l.cout;
+        hipLaunchKernelGGL(k_mask, dim3(nblk(nout)), dim3(256), 0, u->stream, (const float*)u->gact[l.out],
+                           (const bf16_t*)u->act[l.out], l.relu, nout, u->G, u->gm32);
+        // bias
+        int nbb = 64;
+        hipLaunchKernelGGL(k_bias_partial, dim3(nbb), dim3(256), 0, u->stream, (const float*)u->gm32, u->act_n[l.out],
+                           l.cout, u->part);
+        hipLaunchKernelGGL(k_sum_cols, dim3(1), dim3(128), 0, u->stream, (const float*)u->part, nbb, l.cout,
+                           u->grads + l.b_off);
+        const bf16_t* a = u->act[l.in_a];
+        const bf16_t* b = l.in_b >= 0 ? u->act[l.in_b] : nullptr;
+        int cin = l.ca + l.cb;
+        // weights
+        if (l.mode == kModeUp2) {
+            for (int par = 0; par < 8; ++par)
+                launch_wgrad(u, l, a, b, 1, par, l.g, u->grads + l.w_off + (int64_t)par * cin * l.cout);
+        } else {
+            launch_wgrad(u, l, a, b, l.taps, 0, l.g, u->grads + l.w_off);
+        }
+        // input gradient
+        if (l.in_a == u->in_t) continue;
+        if (l.mode == kModeSame3) {
+            Geo g = l.g;  // same grid in and out
+            float* dst = l.in_b >= 0 ? u->tmp32 : u->gact[l.in_a];
+            launch_conv(u, l, u->G, nullptr, l.wb, l.cout, 0, cin, 27 * l.cout, l.Kb, kModeSame3, 0, 1, 0, g, nullptr,
+                        nullptr, dst, l.in_b >= 0 ? 0 : 1);
+            if (l.in_b >= 0) {
+                int64_t nv = u->act_n[l.in_a];
+                hipLaunchKernelGGL(k_split_add, dim3(nblk(nv * cin)), dim3(256), 0, u->stream, (const float*)u->tmp32, nv,
+                                   l.ca, l.cb, u->gact[l.in_a], u->gact[l.in_b]);
+            }
+        } else if (l.mode == kModeDown2) {
+            // rows: coarse voxels of the output; each parity writes its fine voxels
+            Geo g = l.g;
+            g.iD = g.D;
+            g.iH = g.H;
+            g.iW = g.W;
+            for (int par = 0; par < 8; ++par)
+                launch_conv(u, l, u->G, nullptr, l.wb + (int64_t)par * cin * l.Kb, l.cout, 0, cin, l.cout, l.Kb,
+                            kModeUp2, 0, 0, par, g, nullptr, nullptr, u->gact[l.in_a], 1);
+        } else {
+            // up convolution: coarse input gradient from the 8 fine children
+            Geo g = l.g;
+            g.iD = 2 * g.D;
+            g.iH = 2 * g.H;
+            g.iW = 2 * g.W;
+            launch_conv(u, l, u->G, nullptr, l.wb, l.cout, 0, cin, 8 * l.cout, l.Kb, kModeDown2, 0, 0, 0, g, nullptr,
+                        nullptr, u->gact[l.in_a], 1);
+        }
+    }
+    if (loss) {
+        std::vector<float> h(nb0);
+        if (hipMemcpyAsync(h.data(), u->loss_part, nb0 * 4, hipMemcpyDeviceToHost, u->stream) != hipSuccess ||
+            hipStreamSynchronize(u->stream) != hipSuccess)
+            return PIC_E_HIP;
+        double s = 0.0;
+        for (unsigned i = 0; i < nb0; ++i) s += h[i];
+        *loss = s / (double)n0;
+    }
+    return hipGetLastError() == hipSuccess && u->err.empty() ? PIC_OK : PIC_E_HIP;
+}
+
+// One Adam step on the fp32 master weights with the current gradients, then
+// the bf16 copies are refreshed.
+pic_status unet_adam_step(unet* u, float lr, float beta1, float beta2, float eps) {
+    if (!u || !(lr > 0)) return PIC_E_INVALID_ARG;
+    u->adam_t += 1;
+    float c1 = 1.f - powf(beta1, (float)u->adam_t), c2 = 1.f - powf(beta2, (float)u->adam_t);
+    hipLaunchKernelGGL(k_adam, dim3(nblk(u->nparams)), dim3(256), 0, u->stream, u->params, (const float*)u->grads,
+                       u->adam_m, u->adam_v, u->nparams, lr, beta1, beta2, eps, c1, c2);
+    pack_weights(u);
+    return hipGetLastError() == hipSuccess ? PIC_OK : PIC_E_HIP;
+}
+
+// Refresh the bf16 weight copies after the caller changed the parameters.
+pic_status unet_sync_params(unet* u) {
+    if (!u) return PIC_E_INVALID_ARG;
+    pack_weights(u);
+    return hipGetLastError() == hipSuccess ? PIC_OK : PIC_E_HIP;
+}
+
+void unet_destroy(unet* u) {
+    if (!u) return;
+    (void)hipStreamSynchronize(u->stream);
+    delete u;
+}
+
+}  // extern "C"
+
+
+// ---------------------------------------------------------------------------
+// Learned warm start and training pairs of a context.
+
+namespace pic {
+
+constexpr double kTwoM40 = 9.094947017729282379e-13;  // 2^-40
+
+// max |rho| per block (integer, exact)
+__global__ void k_absmax_part(const int64_t* __restrict__ rho, int64_t n, unsigned long long* part) {
+    unsigned long long m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t v = rho[i];
+        unsigned long long a = (unsigned long long)(v < 0 ? -v : v);
+        m = a > m ? a : m;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long t = __shfl_xor(m, o);
+        m = t > m ? t : m;
+    }
+    __shared__ unsigned long long sh[kBlock / 64];
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x / 64); ++w) m = sh[w] > m ? sh[w] : m;
+        part[blockIdx.x] = m;
+    }
+}
+
+__global__ void k_absmax_final(const unsigned long long* part, int nparts, DevState* st) {
+    unsigned long long m = 0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) m = part[i] > m ? part[i] : m;
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long t = __shfl_xor(m, o);
+        m = t > m ? t : m;
+    }
+    if (threadIdx.x == 0) st->learn_scale = (double)m * kTwoM40;
+}
+
+// x = q / s (zero without charge)
+__global__ void k_learn_input(const int64_t* __restrict__ rho, int64_t n, const DevState* st, float* __restrict__ x) {
+    double s = st->learn_scale;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = s > 0.0 ? (float)((double)rho[i] * kTwoM40 / s) : 0.f;
+}
+
+// yo = binomial [1 2 1]/4 filter of yi along x, y and z (edges replicated):
+// removes the node-scale (checkerboard) part of the network's output, which
+// the operator would otherwise turn into a large residual.
+__global__ void k_learn_smooth(const float* __restrict__ yi, float* __restrict__ yo, int nx, int ny, int nz) {
+    int64_t n = (int64_t)nx * ny * nz;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        int x = (int)(i % nx), y = (int)((i / nx) % ny), z = (int)(i / ((int64_t)nx * ny));
+        float acc = 0.f;
+        for (int dz = -1; dz <= 1; ++dz) {
+            int zz = min(max(z + dz, 0), nz - 1);
+            float wz = dz == 0 ? 0.5f : 0.25f;
+            for (int dy = -1; dy <= 1; ++dy) {
+                int yy = min(max(y + dy, 0), ny - 1);
+                float wy = dy == 0 ? 0.5f : 0.25f;
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int xx = min(max(x + dx, 0), nx - 1);
+                    float wx = dx == 0 ? 0.5f : 0.25f;
+                    acc += wz * wy * wx * yi[((int64_t)zz * ny + yy) * nx + xx];
+                }
+            }
+        }
+        yo[i] = acc;
+    }
+}
+
+// phi = V0 phi1 + (e s / (eps0 h)) y on free nodes, V0 phi1 on fixed nodes
+__global__ void k_learn_phi(const double* __restrict__ phi1, const float* __restrict__ y, const uint8_t* __restrict__ type,
+                            int64_t n, double V0, double c0, const DevState* st, double* __restrict__ phi) {
+    double s = st->learn_scale;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double v = V0 * phi1[i];
+        if (y && type[i] == 0 && s > 0.0) v += c0 * s * (double)y[i];
+        phi[i] = v;
+    }
+}
+
+// y = (phi - V0 phi1) eps0 h / (e s) on free nodes, zero elsewhere
+__global__ void k_learn_target(const double* __restrict__ phi, const double* __restrict__ phi1,
+                               const uint8_t* __restrict__ type, int64_t n, double V0, double c1, const DevState* st,
+                               float* __restrict__ y) {
+    double s = st->learn_scale;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = (s > 0.0 && type[i] == 0) ? (float)((phi[i] - V0 * phi1[i]) * c1 / s) : 0.f;
+}
+
+static hipError_t learn_scale_and_input(pic_ctx* c, float* x) {
+    int64_t n = c->g.nn;
+    unsigned G = 1024;
+    unsigned long long* part = (unsigned long long*)c->partials;
+    hipLaunchKernelGGL(k_absmax_part, dim3(G), dim3(kBlock), 0, c->stream, (const int64_t*)c->buf.rho, n, part);
+    hipLaunchKernelGGL(k_absmax_final, dim3(1), dim3(64), 0, c->stream, (const unsigned long long*)part, (int)G, c->st);
+    if (x) hipLaunchKernelGGL(k_learn_input, dim3(4096), dim3(kBlock), 0, c->stream, (const int64_t*)c->buf.rho, n,
+                              (const pic::DevState*)c->st, x);
+    return hipGetLastError();
+}
+
+int guess_phi(pic_ctx* c, bool with_net) {
+    int64_t n = c->g.nn;
+    const float* y = nullptr;
+    if (with_net) {
+        // network input and output in the (idle) CG work vectors
+        float* x = (float*)c->cg_p0;
+        float* yo = (float*)c->cg_q;
+        if (learn_scale_and_input(c, x) != hipSuccess) return -2;
+        if (unet_forward(c->learned, x, yo) != PIC_OK) return -2;
+        float* a = yo;
+        float* b = x;  // the input is no longer needed
+        for (int k = 0; k < c->learn_smooth; ++k) {
+            hipLaunchKernelGGL(k_learn_smooth, dim3(4096), dim3(kBlock), 0, c->stream, (const float*)a, b, c->cfg.nx,
+                               c->cfg.ny, c->cfg.nz);
+            std::swap(a, b);
+        }
+        y = a;
+    }
+    double c0 = kQe / (kEps0 * c->cfg.h);
+    hipLaunchKernelGGL(k_learn_phi, dim3(4096), dim3(kBlock), 0, c->stream, (const double*)c->buf.phi1, y,
+                       (const uint8_t*)c->buf.node_type, n, c->V0, c0, (const pic::DevState*)c->st,
+                       (double*)c->buf.phi);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+}  // namespace pic
+
+extern "C" {
+
+pic_status pic_set_learned_guess(pic_ctx* c, unet* u, int32_t smooth_passes) {
+    if (!c || smooth_passes < 0 || smooth_passes > 64) return PIC_E_INVALID_ARG;
+    if (u && (u->B != 1 || u->D != c->cfg.nz || u->H != c->cfg.ny || u->W != c->cfg.nx || u->stream != c->stream))
+        return PIC_E_INVALID_ARG;
+    c->learned = u;
+    c->learn_smooth = smooth_passes;
+    return PIC_OK;
+}
+
+pic_status pic_training_sample(pic_ctx* c, float* x, float* y, double* scale) {
+    if (!c || !x || !y) return PIC_E_INVALID_ARG;
+    if (c->failed) return PIC_E_STATE;
+    if (pic::learn_scale_and_input(c, x) != hipSuccess) return PIC_E_HIP;
+    double c1 = pic::kEps0 * c->cfg.h / pic::kQe;
+    hipLaunchKernelGGL(pic::k_learn_target, dim3(4096), dim3(pic::kBlock), 0, c->stream, (const double*)c->buf.phi,
+                       (const double*)c->buf.phi1, (const uint8_t*)c->buf.node_type, c->g.nn, c->V0, c1,
+                       (const pic::DevState*)c->st, y);
+    if (hipGetLastError() != hipSuccess) return PIC_E_HIP;
+    if (scale) {
+        double s = 0.0;
+        if (hipMemcpyAsync(&s, &c->st->learn_scale, sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            return PIC_E_HIP;
+        *scale = s;
+    }
+    return PIC_OK;
+}
+
+}  // extern "C"

@@ -25,7 +25,7 @@ PIC_OK = 0
 ERRORS = {-1: "INVALID_ARG", -2: "HIP", -3: "CAPACITY", -4: "OVERFLOW", -5: "NOT_CONVERGED", -6: "STATE"}
 PIC_F64, PIC_F32 = 0, 1
 PIC_SOLVER_CG, PIC_SOLVER_MGCG, PIC_SOLVER_MIXED = 0, 1, 2
-PIC_GUESS_ZERO, PIC_GUESS_PREVIOUS = 0, 1
+PIC_GUESS_ZERO, PIC_GUESS_PREVIOUS, PIC_GUESS_LAPLACE, PIC_GUESS_LEARNED = 0, 1, 2, 3
 STEP_INJECT, STEP_PUSH, STEP_DEPOSIT, STEP_COLLIDE = 0x01, 0x02, 0x04, 0x08
 STEP_SOLVE, STEP_FIELD, STEP_ADVANCE, STEP_EVENTS = 0x10, 0x20, 0x40, 0x80
 STEP_FULL = STEP_INJECT | STEP_PUSH | STEP_COLLIDE | STEP_SOLVE | STEP_ADVANCE
@@ -75,6 +75,10 @@ class pic_moments_t(C.Structure):
                 ("last_cg_relres", C.c_double), ("cg_iters_total", C.c_int64)]
 
 
+class pic_unet_config(C.Structure):
+    _fields_ = [("base_channels", C.c_int32), ("reserved", C.c_int32 * 7)]
+
+
 class pic_event(C.Structure):
     _fields_ = [("kind", C.c_int32), ("id_a", C.c_uint32), ("id_b", C.c_uint32), ("new_ion", C.c_uint32),
                 ("new_e", C.c_uint32)]
@@ -106,8 +110,23 @@ def lib():
         L.pic_last_error.restype = C.c_char_p
         L.pic_destroy.argtypes = [vp]
         L.pic_destroy.restype = None
+        up = C.POINTER(pic_unet_config)
+        L.unet_param_count.argtypes = [up, C.POINTER(C.c_int64)]
+        L.unet_workspace_size.argtypes = [up, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)]
+        L.unet_create.argtypes = [up, vp, vp, vp, C.c_size_t, C.c_int32, C.c_int32, C.c_int32, C.c_int32, vp,
+                                  C.POINTER(vp)]
+        L.unet_forward.argtypes = [vp, vp, vp]
+        L.unet_backward.argtypes = [vp, vp, C.POINTER(C.c_double)]
+        L.unet_adam_step.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float]
+        L.unet_sync_params.argtypes = [vp]
+        L.unet_destroy.argtypes = [vp]
+        L.unet_destroy.restype = None
+        L.pic_set_learned_guess.argtypes = [vp, vp, C.c_int32]
+        L.pic_training_sample.argtypes = [vp, vp, vp, C.POINTER(C.c_double)]
         for f in ("pic_scratch_size", "pic_init", "pic_inject", "pic_step", "pic_solve_poisson", "pic_moments",
-                  "pic_events"):
+                  "pic_events", "unet_param_count", "unet_workspace_size", "unet_create", "unet_forward",
+                  "unet_backward", "unet_adam_step", "unet_sync_params", "pic_set_learned_guess",
+                  "pic_training_sample"):
             getattr(L, f).restype = C.c_int32
         _lib = L
     return _lib
@@ -201,6 +220,57 @@ def pic_destroy(ctx):
 
 # --------------------------------------------------------------------------
 # Memory plumbing: one instance with torch-owned device buffers
+
+
+def unet_param_count(cfg: pic_unet_config) -> int:
+    n = C.c_int64()
+    _check(lib().unet_param_count(C.byref(cfg), C.byref(n)))
+    return n.value
+
+
+def unet_workspace_size(cfg: pic_unet_config, batch: int, d: int, h: int, w: int) -> int:
+    n = C.c_size_t()
+    _check(lib().unet_workspace_size(C.byref(cfg), batch, d, h, w, C.byref(n)))
+    return n.value
+
+
+def unet_create(cfg, params: int, grads: int, workspace: int, ws_bytes: int, batch, d, h, w, stream: int):
+    out = C.c_void_p()
+    _check(lib().unet_create(C.byref(cfg), params, grads, workspace, ws_bytes, batch, d, h, w, stream,
+                             C.byref(out)))
+    return out.value
+
+
+def unet_forward(net, x: int, y: int | None):
+    _check(lib().unet_forward(net, x, y))
+
+
+def unet_backward(net, target: int, want_loss: bool = True) -> float | None:
+    loss = C.c_double()
+    _check(lib().unet_backward(net, target, C.byref(loss) if want_loss else None))
+    return loss.value if want_loss else None
+
+
+def unet_adam_step(net, lr: float, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib().unet_adam_step(net, lr, beta1, beta2, eps))
+
+
+def unet_sync_params(net):
+    _check(lib().unet_sync_params(net))
+
+
+def unet_destroy(net):
+    lib().unet_destroy(net)
+
+
+def pic_set_learned_guess(ctx, net, smooth_passes: int = 0):
+    _check(lib().pic_set_learned_guess(ctx, net, smooth_passes), ctx)
+
+
+def pic_training_sample(ctx, x: int, y: int) -> float:
+    s = C.c_double()
+    _check(lib().pic_training_sample(ctx, x, y, C.byref(s)), ctx)
+    return s.value
 
 
 def make_config(cfg: workloads.Config, precision=PIC_F64, solver=PIC_SOLVER_CG, laplace_rtol=1e-13,
@@ -330,3 +400,99 @@ class Simulation:
         t = getattr(self, name)
         torch.cuda.synchronize(self.device)
         return t.cpu().numpy()
+
+
+class UNet:
+    """The warm-start network of include/pic.h on torch-owned device memory:
+    fp32 parameters and gradients, and the work memory."""
+
+    def __init__(self, batch: int, d: int, h: int, w: int, base_channels: int = 16, seed: int = 0,
+                 params: torch.Tensor | None = None, device="cuda"):
+        self.cfg = pic_unet_config(base_channels=base_channels)
+        self.shape = (batch, d, h, w)
+        self.device = torch.device(device)
+        self.n_params = unet_param_count(self.cfg)
+        if params is None:
+            params = init_unet_params(self.layers(), self.n_params, seed)
+        self.params = torch.as_tensor(params, dtype=torch.float32).to(self.device).contiguous()
+        self.grads = torch.zeros_like(self.params)
+        nb = unet_workspace_size(self.cfg, batch, d, h, w)
+        self._ws = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        off = (-self._ws.data_ptr()) % 256
+        self.stream = torch.cuda.current_stream(self.device)
+        torch.cuda.synchronize(self.device)
+        self.net = unet_create(self.cfg, self.params.data_ptr(), self.grads.data_ptr(), self._ws.data_ptr() + off, nb,
+                               batch, d, h, w, self.stream.cuda_stream)
+
+    def layers(self):
+        return unet_layers(self.cfg.base_channels)
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        x = x.to(self.device, torch.float32).contiguous()
+        assert tuple(x.shape) == self.shape
+        y = torch.empty_like(x)
+        unet_forward(self.net, x.data_ptr(), y.data_ptr())
+        return y
+
+    def train_step(self, x: torch.Tensor, target: torch.Tensor, lr: float, want_loss=True):
+        x = x.to(self.device, torch.float32).contiguous()
+        target = target.to(self.device, torch.float32).contiguous()
+        assert tuple(x.shape) == self.shape and tuple(target.shape) == self.shape
+        unet_forward(self.net, x.data_ptr(), None)
+        loss = unet_backward(self.net, target.data_ptr(), want_loss)
+        unet_adam_step(self.net, lr)
+        return loss
+
+    def gradients(self, x: torch.Tensor, target: torch.Tensor) -> tuple[float, torch.Tensor]:
+        x = x.to(self.device, torch.float32).contiguous()
+        target = target.to(self.device, torch.float32).contiguous()
+        unet_forward(self.net, x.data_ptr(), None)
+        loss = unet_backward(self.net, target.data_ptr(), True)
+        return loss, self.grads.clone()
+
+    def sync(self):
+        torch.cuda.synchronize(self.device)
+        unet_sync_params(self.net)
+
+    def close(self):
+        if self.net is not None:
+            torch.cuda.synchronize(self.device)
+            unet_destroy(self.net)
+            self.net = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def unet_layers(base: int = 16):
+    """(kind, cin, cout) of every layer in parameter order, then the head;
+    kind is "conv3" (3x3x3), "down" (2x2x2 stride 2) or "up" (2x2x2 stride-2
+    transposed). This is the layout of the parameter vector in include/pic.h."""
+    c = [base, 2 * base, 4 * base, 8 * base]
+    L = [("conv3", 8, c[0]), ("conv3", c[0], c[0])]
+    for lv in range(1, 4):
+        L += [("down", c[lv - 1], c[lv]), ("conv3", c[lv], c[lv]), ("conv3", c[lv], c[lv])]
+    for lv in (2, 1, 0):
+        L += [("up", c[lv + 1], c[lv]), ("conv3", 2 * c[lv], c[lv]), ("conv3", c[lv], c[lv])]
+    return L
+
+
+def init_unet_params(layers, n_params: int, seed: int) -> np.ndarray:
+    """He-normal weights (fan-in = taps x cin), zero biases, head weights of
+    scale 1/sqrt(cin). The first layer's fan-in counts its one live channel."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i, (kind, cin, cout) in enumerate(layers):
+        taps = 27 if kind == "conv3" else 8
+        fan = taps * (1 if i == 0 else cin) if kind != "up" else cin
+        out.append(rng.standard_normal(taps * cin * cout) * np.sqrt(2.0 / fan))
+        out.append(np.zeros(cout))
+    base = layers[-1][2]
+    out.append(rng.standard_normal(base) / np.sqrt(base))
+    out.append(np.zeros(1))
+    p = np.concatenate(out).astype(np.float32)
+    assert p.size == n_params, (p.size, n_params)
+    return p
