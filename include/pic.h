@@ -215,8 +215,11 @@ pic_status pic_moments(pic_ctx* ctx, pic_moments_t* out);
 pic_status pic_events(pic_ctx* ctx, pic_event* out, int64_t cap, int64_t* n);
 
 /* Timers. With profiling enabled, pic_step and pic_solve_poisson record HIP
- * events on the context stream around each phase and around the hot kernels;
- * pic_timers adds up the elapsed times since the last reset (synchronizes). */
+ * events on the context stream around each phase and around the hot kernels
+ * (the kernels of the first 64 solver iterations of each solve), and the
+ * multigrid solver launches its iterations one by one instead of as a
+ * captured graph; pic_timers adds up the elapsed times since the last reset
+ * (synchronizes). */
 #define PIC_T_INJECT 0        /* emission phase */
 #define PIC_T_PUSH_E 1        /* electron push kernel (gather, push, deposit, binning) */
 #define PIC_T_PUSH 2          /* the three push kernels */
@@ -230,7 +233,11 @@ pic_status pic_events(pic_ctx* ctx, pic_event* out, int64_t cap, int64_t* n);
 #define PIC_T_MG 10           /* multigrid V-cycles */
 #define PIC_T_DEPOSIT 11      /* tiled charge deposit kernel */
 #define PIC_T_BIN 12          /* cell bins (radix sort of the cell keys) */
-#define PIC_NTIMERS 13
+#define PIC_T_MG_FIRST 13     /* finest-level pre-smoothing kernel (two sweeps from zero) */
+#define PIC_T_MG_RESTRICT 14  /* finest-level residual restriction kernel */
+#define PIC_T_MG_CORR 15      /* finest-level coarse correction + sweep kernel */
+#define PIC_T_MG_LAST 16      /* finest-level last sweep kernel (with the r.z partials) */
+#define PIC_NTIMERS 17
 
 pic_status pic_profile(pic_ctx* ctx, int32_t enable);
 /* ms[PIC_NTIMERS]: summed milliseconds; count[PIC_NTIMERS]: number of timed

@@ -245,18 +245,8 @@ __device__ inline void node_ijk(const Grid& g, int64_t n, int& i, int& j, int& k
     k = (int)(n / ((int64_t)g.nx * g.ny));
 }
 
-// Sum of kCgBlocks partials in a fixed order; the result is returned to every
-// thread of the block.
-__device__ inline double sum_partials(const double* part) {
-    __shared__ double sh[kBlock / 64];
-    __shared__ double res;
-    double v = 0.0;
-    for (int i = threadIdx.x; i < kCgBlocks; i += blockDim.x) v += part[i];
-    double t = block_sum(v, sh);
-    if (threadIdx.x == 0) res = t;
-    __syncthreads();
-    return res;
-}
+// Sum of the kCgBlocks partials of the previous kernel, in a fixed order.
+__device__ inline double sum_partials(const double* part) { return sum_partials_n(part, kCgBlocks); }
 
 __device__ inline void write_partial(double v, double* part) {
     __shared__ double sh[kBlock / 64];
@@ -390,8 +380,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_b(CgArgs a, int it) {
     int64_t b0 = xcd_block(blockIdx.x, gridDim.x) * a.chunk;
     int64_t b1 = b0 + a.chunk < g.nn ? b0 + a.chunk : g.nn;
     double rr = 0.0;
+    // p and q are zero on fixed nodes, so x and r keep their values there
+    // and no node type is needed
     for (int64_t n = b0 + threadIdx.x; n < b1; n += blockDim.x) {
-        if (a.type[n] != 0) continue;
         double p = a.p_new[n];
         a.x[n] += alpha * p;
         double r = a.r[n] - alpha * a.q[n];
@@ -482,64 +473,73 @@ int cg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess, 
 // V-cycle (its first kernel finishes r.r and tests convergence, its last
 // writes the partials of r.z), then k_pcg_a (beta from r.z, p = z + beta p,
 // q = A p, partials of p.q) and k_pcg_b (alpha, x and r update, partials of
-// r.r).
+// r.r). The iteration count and the previous r.z live on the device, so every
+// iteration launches the same kernels with the same arguments.
 
+// z-marching: p = z + beta p_old at the node and its six neighbours, q = A p.
 __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs a, const double* __restrict__ z, const double* part_rz,
-                                                   int it) {
+                                                   int n_rz, int kc) {
     DevState* s = a.s;
     if (s->done) return;
     const Grid& g = a.g;
-    double rz = sum_partials(part_rz);
-    double beta = it == 0 ? 0.0 : rz / s->rzbuf[(it - 1) & 1];
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        s->rzbuf[it & 1] = rz;
-        s->it = it;
-    }
-    int64_t b0 = xcd_block(blockIdx.x, gridDim.x) * a.chunk;
-    int64_t b1 = b0 + a.chunk < g.nn ? b0 + a.chunk : g.nn;
-    int64_t pl = (int64_t)g.nx * g.ny;
+    double rz = sum_partials_n(part_rz, n_rz);
+    double beta = s->it == 0 ? 0.0 : rz / s->rz_prev;
+    const double* __restrict__ po = a.p_old;
+    auto pv = [&](int64_t m) { return z[m] + beta * po[m]; };  // zero on fixed nodes
+    ZMarch t = zmarch(g.nx, g.ny, g.nz, kc);
     double pq = 0.0;
-    NodeWalk wk(b0 + threadIdx.x, blockDim.x, g.nx, g.ny);
-    for (int64_t n = b0 + threadIdx.x; n < b1; n += blockDim.x, wk.advance()) {
-        if (a.type[n] != 0) {
-            a.p_new[n] = 0.0;
-            a.q[n] = 0.0;
-            continue;
+    if (t.col) {
+        int i = t.i, j = t.j;
+        int64_t pl = (int64_t)g.nx * g.ny;
+        int64_t n = (int64_t)t.k0 * pl + (int64_t)j * g.nx + i;
+        double hx = half_at_edge(i, g.nx), hy = half_at_edge(j, g.ny), fz = hx * hy;
+        // neighbours outside the grid are read at the node itself with a zero
+        // weight: every load is unconditional, so a step's loads issue together
+        const int64_t ow = i > 0 ? -1 : 0, oe = i < g.nx - 1 ? 1 : 0;
+        const int64_t os = j > 0 ? -(int64_t)g.nx : 0, on = j < g.ny - 1 ? (int64_t)g.nx : 0;
+        // a free node is never on a z face: fx = hy, fy = hx
+        const double ww = i > 0 ? hy : 0.0, we = i < g.nx - 1 ? hy : 0.0;
+        const double ws = j > 0 ? hx : 0.0, wn = j < g.ny - 1 ? hx : 0.0;
+        double pm = pv(t.k0 > 0 ? n - pl : n);
+        if (t.k0 == 0) pm = 0.0;
+        double pc = pv(n);
+        for (int k = t.k0; k < t.k1; ++k, n += pl) {
+            const bool up = k + 1 < g.nz;
+            double pp = pv(up ? n + pl : n);
+            if (!up) pp = 0.0;
+            const double xw = pv(n + ow), xe = pv(n + oe), xs = pv(n + os), xn = pv(n + on);
+            const bool fr = a.type[n] == 0;
+            double acc = 0.0;
+            acc += ww * (pc - xw);
+            acc += we * (pc - xe);
+            acc += ws * (pc - xs);
+            acc += wn * (pc - xn);
+            acc += fz * (pc - pm);
+            acc += fz * (pc - pp);
+            const double qv = fr ? acc : 0.0;
+            pq += pc * qv;
+            a.p_new[n] = pc;
+            a.q[n] = qv;
+            pm = pc;
+            pc = pp;
         }
-        int i = wk.i, j = wk.j, k = wk.k;
-        double fx = half_at_edge(j, g.ny) * half_at_edge(k, g.nz);
-        double fy = half_at_edge(i, g.nx) * half_at_edge(k, g.nz);
-        double fz = half_at_edge(i, g.nx) * half_at_edge(j, g.ny);
-        double pi = z[n] + beta * a.p_old[n];
-        double acc = 0.0;
-        int64_t nb[6] = {n - 1, n + 1, n - g.nx, n + g.nx, n - pl, n + pl};
-        bool has[6] = {i > 0, i < g.nx - 1, j > 0, j < g.ny - 1, true, true};
-        double f[6] = {fx, fx, fy, fy, fz, fz};
-#pragma unroll
-        for (int d = 0; d < 6; ++d) {
-            if (!has[d]) continue;
-            int64_t m = nb[d];
-            double pj = z[m] + beta * a.p_old[m];  // z and p are zero on fixed nodes
-            acc += f[d] * (pi - pj);
-        }
-        a.p_new[n] = pi;
-        a.q[n] = acc;
-        pq += pi * acc;
     }
     write_partial(pq, a.part_pq);
 }
 
-__global__ __launch_bounds__(kBlock) void k_pcg_b(CgArgs a, int it) {
+__global__ __launch_bounds__(kBlock) void k_pcg_b(CgArgs a, const double* part_rz, int n_rz, int n_pq) {
     DevState* s = a.s;
     if (s->done) return;
     const Grid& g = a.g;
-    double pq = sum_partials(a.part_pq);
-    double alpha = s->rzbuf[it & 1] / pq;
+    double rz = sum_partials_n(part_rz, n_rz);
+    double pq = sum_partials_n(a.part_pq, n_pq);
+    double alpha = rz / pq;
     int64_t b0 = xcd_block(blockIdx.x, gridDim.x) * a.chunk;
     int64_t b1 = b0 + a.chunk < g.nn ? b0 + a.chunk : g.nn;
     double rr = 0.0;
+    // p and q are zero on fixed nodes, so x and r keep their values there
+    // and no node type is needed
     for (int64_t n = b0 + threadIdx.x; n < b1; n += blockDim.x) {
-        if (a.type[n] != 0) continue;
         double p = a.p_new[n];
         a.x[n] += alpha * p;
         double r = a.r[n] - alpha * a.q[n];
@@ -547,7 +547,11 @@ __global__ __launch_bounds__(kBlock) void k_pcg_b(CgArgs a, int it) {
         rr += r * r;
     }
     write_partial(rr, a.part_rr);
-    if (blockIdx.x == 0 && threadIdx.x == 0) s->it = it + 1;
+    // only this block reads or writes the iteration state in this kernel
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s->rz_prev = rz;
+        s->it = s->it + 1;
+    }
 }
 
 int mgcg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess, double rtol, int maxit,
@@ -568,35 +572,68 @@ int mgcg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess
     a.V0 = V0;
     a.s = c->st;
     a.part_pq = c->partials;
-    a.part_rr = c->partials + kCgBlocks;
-    a.part_bb = c->partials + 2 * kCgBlocks;
-    double* part_rz = c->partials + 3 * kCgBlocks;
+    a.part_rr = c->partials + 2048;
+    a.part_bb = c->partials + 4096;
+    double* part_rz = c->partials + 6144;
     a.chunk = ((g.nn + kCgBlocks - 1) / kCgBlocks + kBlock - 1) / kBlock * kBlock;
+    int kc = 1;
+    unsigned zb = zmarch_grid(g.nx, g.ny, g.nz, kCgBlocks, 1, &kc);
+    if (zb > 2048) return -3;
     hipLaunchKernelGGL(k_cg_setup, dim3(1), dim3(1), 0, c->stream, c->st, rtol, maxit);
     hipLaunchKernelGGL(k_cg_init, dim3((unsigned)G), dim3(kBlock), 0, c->stream, a, guess == PIC_GUESS_ZERO);
     hipLaunchKernelGGL(k_cg_resid, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a);
-    double* pa = c->cg_p0;
-    double* pb = c->cg_p1;
+    // one iteration: V-cycle, p update and A p, x and r update
+    auto iteration = [&](double* p_old, double* p_new, bool timed) {
+        int tm = timed ? tic(c, PIC_T_MG) : -1;
+        int n_rz = 0;
+        double* z = mg_vcycle(c, a.part_rr, a.part_bb, part_rz, kCgBlocks, &n_rz, timed);
+        toc(c, tm);
+        a.p_old = p_old;
+        a.p_new = p_new;
+        int ta = timed ? tic(c, PIC_T_CG_A) : -1;
+        hipLaunchKernelGGL(k_pcg_a, dim3(zb), dim3(kBlock), 0, c->stream, a, (const double*)z, (const double*)part_rz,
+                           n_rz, kc);
+        toc(c, ta);
+        int tb = timed ? tic(c, PIC_T_CG_B) : -1;
+        hipLaunchKernelGGL(k_pcg_b, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a, (const double*)part_rz, n_rz,
+                           (int)zb);
+        toc(c, tb);
+    };
+    // Without profiling, pairs of iterations run as one captured graph (the
+    // kernels read the iteration state from the device, so every pair is
+    // the same launch sequence; p ping-pongs p0 -> p1 -> p0 within a pair).
+    bool use_graph = !c->prof;
+    if (use_graph && !c->pcg_exec) {
+        bool ok = true;
+        if (!c->cap_stream) ok = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
+        hipStream_t keep = c->stream;
+        if (ok) ok = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            c->stream = c->cap_stream;
+            iteration(c->cg_p0, c->cg_p1, false);
+            iteration(c->cg_p1, c->cg_p0, false);
+            c->stream = keep;
+            hipGraph_t gr = nullptr;
+            ok = hipStreamEndCapture(c->cap_stream, &gr) == hipSuccess && gr;
+            if (ok) ok = hipGraphInstantiate(&c->pcg_exec, gr, nullptr, nullptr, 0) == hipSuccess;
+            if (ok) c->pcg_graph = gr;
+            else if (gr) (void)hipGraphDestroy(gr);
+        }
+        if (!ok) {
+            c->stream = keep;
+            (void)hipGetLastError();
+            return -2;
+        }
+    }
     int chunk = 2;
     int it = 0;
     while (true) {
-        for (int t = 0; t < chunk && it <= maxit; ++t, ++it) {
-            int tm = it < 64 ? tic(c, PIC_T_MG) : -1;
-            double* z = mg_vcycle(c, a.part_rr, a.part_bb, part_rz, kCgBlocks);
-            toc(c, tm);
-            if (it == maxit) continue;
-            a.p_old = pa;
-            a.p_new = pb;
-            int ta = it < 64 ? tic(c, PIC_T_CG_A) : -1;
-            hipLaunchKernelGGL(k_pcg_a, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a, (const double*)z,
-                               (const double*)part_rz, it);
-            toc(c, ta);
-            int tb = it < 64 ? tic(c, PIC_T_CG_B) : -1;
-            hipLaunchKernelGGL(k_pcg_b, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a, it);
-            toc(c, tb);
-            double* t2 = pa;
-            pa = pb;
-            pb = t2;
+        if (use_graph) {
+            for (int t = 0; t < chunk && it <= maxit; t += 2, it += 2)
+                if (hipGraphLaunch(c->pcg_exec, c->stream) != hipSuccess) return -2;
+        } else {
+            for (int t = 0; t < chunk && it <= maxit; ++t, ++it)
+                iteration((it & 1) ? c->cg_p1 : c->cg_p0, (it & 1) ? c->cg_p0 : c->cg_p1, it < 64);
         }
         (void)hipMemcpyAsync(c->host_st, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream);
         if (hipStreamSynchronize(c->stream) != hipSuccess) return -2;

@@ -9,7 +9,10 @@
 // uses the operator matrix-free from the node types; coarser levels store
 // diag and the +x/+y/+z couplings per node. Smoother: damped Jacobi, the same
 // number of sweeps before and after the coarse correction, so the V-cycle is
-// a symmetric positive definite preconditioner for CG.
+// a symmetric positive definite preconditioner for CG. The coarsest level
+// (at most 1024 nodes) is solved exactly with its inverse, formed once on the
+// host at set-up. The finest level runs as z-marching kernels.
+#include <cmath>
 #include <vector>
 
 #include "pic_internal.hpp"
@@ -19,7 +22,6 @@ namespace pic {
 constexpr int kMgMaxLevels = 12;
 constexpr int kMgBlocks = 1024;
 constexpr double kOmega = 6.0 / 7.0;  // damped Jacobi weight for 7-point stencils
-constexpr int kCoarseSweeps = 64;
 
 struct MgLevel {
     int nx, ny, nz;
@@ -33,8 +35,11 @@ struct MgHier {
     MgLevel lv[kMgMaxLevels];
     double* z[2];  // finest-level preconditioned residual (ping-pong)
     double* part;  // partial sums
+    double* cinv;  // inverse of the coarsest operator, n x n (zero rows / columns for fixed nodes)
     int pre, post;
     double alpha_c;
+    int zm_kc, zr_kc;          // planes per block of the fine sweeps / the fine restriction
+    unsigned zm_blocks, zr_blocks;
 };
 
 static void mg_dims(const pic_config* cfg, std::vector<int3>& dims) {
@@ -57,6 +62,8 @@ size_t mg_bytes(const pic_config* cfg) {
         int64_t n = (int64_t)dims[l].x * dims[l].y * dims[l].z;
         b += 7 * (size_t)n * 8 + 7 * 256;
     }
+    int64_t nc = (int64_t)dims.back().x * dims.back().y * dims.back().z;
+    if (nc <= 1024) b += (size_t)nc * nc * 8 + 256;
     return b;
 }
 
@@ -71,7 +78,6 @@ __global__ void k_mg_build1(Grid g, const uint8_t* __restrict__ type, MgLevel c)
     if (I >= c.n) return;
     int Ix = (int)(I % c.nx), Iy = (int)((I / c.nx) % c.ny), Iz = (int)(I / ((int64_t)c.nx * c.ny));
     double dg = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
-    int64_t pl = (int64_t)g.nx * g.ny;
     for (int t = 0; t < 8; ++t) {
         int i = 2 * Ix + (t & 1), j = 2 * Iy + ((t >> 1) & 1), k = 2 * Iz + ((t >> 2) & 1);
         if (i >= g.nx || j >= g.ny || k >= g.nz) continue;
@@ -135,36 +141,23 @@ __global__ void k_mg_build(MgLevel f, MgLevel c) {
 // ---------------------------------------------------------------------------
 // Operator application
 
-// Finest level, matrix free: returns (A x)_n and the diagonal. x must be zero
-// on nodes held at a fixed potential (true for every multigrid vector).
-__device__ inline double apply_fine(const Grid& g, const uint8_t* __restrict__ type, const double* __restrict__ x,
-                                    int64_t n, int i, int j, int k, double xn, double* dg) {
-    int64_t pl = (int64_t)g.nx * g.ny;
-    double fx = hedge(j, g.ny) * hedge(k, g.nz), fy = hedge(i, g.nx) * hedge(k, g.nz), fz = hedge(i, g.nx) * hedge(j, g.ny);
-    int64_t nb[6] = {n - 1, n + 1, n - g.nx, n + g.nx, n - pl, n + pl};
-    bool has[6] = {i > 0, i < g.nx - 1, j > 0, j < g.ny - 1, k > 0, k < g.nz - 1};
-    double f[6] = {fx, fx, fy, fy, fz, fz};
-    double acc = 0.0, d = 0.0;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
-        if (!has[q]) continue;
-        d += f[q];
-        acc += f[q] * (xn - x[nb[q]]);
-    }
-    *dg = d;
-    return acc;
-}
-
+// (A x)_n on a coarse level. Neighbours outside the grid are read at the node
+// itself with a zero coefficient, so all loads are unconditional.
 __device__ inline double apply_coarse(const MgLevel& L, const double* __restrict__ x, int64_t n, int i, int j, int k,
                                       double xn) {
     int64_t pl = (int64_t)L.nx * L.ny;
+    const int64_t ow = i > 0 ? -1 : 0, oe = i < L.nx - 1 ? 1 : 0;
+    const int64_t os = j > 0 ? -(int64_t)L.nx : 0, on = j < L.ny - 1 ? (int64_t)L.nx : 0;
+    const int64_t ob = k > 0 ? -pl : 0, ot = k < L.nz - 1 ? pl : 0;
+    const double cw = L.cx[n + ow], ce = L.cx[n], cs = L.cy[n + os], cn = L.cy[n], cb = L.cz[n + ob], ct = L.cz[n];
+    const double xw = x[n + ow], xe = x[n + oe], xs = x[n + os], xnn = x[n + on], xb = x[n + ob], xt = x[n + ot];
     double s = L.diag[n] * xn;
-    if (i > 0) s += L.cx[n - 1] * x[n - 1];
-    if (i < L.nx - 1) s += L.cx[n] * x[n + 1];
-    if (j > 0) s += L.cy[n - L.nx] * x[n - L.nx];
-    if (j < L.ny - 1) s += L.cy[n] * x[n + L.nx];
-    if (k > 0) s += L.cz[n - pl] * x[n - pl];
-    if (k < L.nz - 1) s += L.cz[n] * x[n + pl];
+    s += (i > 0 ? cw : 0.0) * xw;
+    s += (i < L.nx - 1 ? ce : 0.0) * xe;
+    s += (j > 0 ? cs : 0.0) * xs;
+    s += (j < L.ny - 1 ? cn : 0.0) * xnn;
+    s += (k > 0 ? cb : 0.0) * xb;
+    s += (k < L.nz - 1 ? ct : 0.0) * xt;
     return s;
 }
 
@@ -180,26 +173,15 @@ struct MgArgs {
     double* part_rz;   // partials of r.z written by the last kernel
 };
 
-__device__ inline double sum_parts(const double* part, int nparts) {
-    __shared__ double sh[kBlock / 64];
-    __shared__ double res;
-    double v = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += blockDim.x) v += part[i];
-    double t = block_sum(v, sh);
-    if (threadIdx.x == 0) res = t;
-    __syncthreads();
-    return res;
-}
-
 // Convergence test of the CG update (one block): finishes r.r (and b.b
 // before the first iteration) and sets done.
 __global__ void k_mg_test(MgArgs a, int cg_blocks) {
     DevState* s = a.s;
     if (s->done) return;
-    double rr = sum_parts(a.part_rr, cg_blocks);
+    double rr = sum_partials_n(a.part_rr, cg_blocks);
     double bb;
     if (s->it == 0) {
-        bb = sum_parts(a.part_bb, cg_blocks);
+        bb = sum_partials_n(a.part_bb, cg_blocks);
         if (threadIdx.x == 0) {
             s->bb = bb;
             s->rr0 = rr;
@@ -217,173 +199,335 @@ __global__ void k_mg_test(MgArgs a, int cg_blocks) {
     }
 }
 
-// First sweep from x = 0: x = omega D^-1 b.
-__global__ __launch_bounds__(kBlock) void k_mg_first(MgArgs a, MgLevel L, int level) {
+// First sweep from x = 0 on a coarse level: x = omega D^-1 b.
+__global__ __launch_bounds__(kBlock) void k_mg_first(MgArgs a, MgLevel L) {
     DevState* s = a.s;
     if (s->done) return;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    NodeWalk wk((int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int)stride, L.nx, L.ny);
-    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < L.n; n += stride, wk.advance()) {
-        double d;
-        if (level == 0) {
-            if (a.type[n] != 0) {
-                L.x0[n] = 0.0;
-                continue;
-            }
-            const Grid& g = a.g;
-            int i = wk.i, j = wk.j, k = wk.k;
-            d = (i > 0 ? hedge(j, g.ny) * hedge(k, g.nz) : 0.0) + (i < g.nx - 1 ? hedge(j, g.ny) * hedge(k, g.nz) : 0.0) +
-                (j > 0 ? hedge(i, g.nx) * hedge(k, g.nz) : 0.0) + (j < g.ny - 1 ? hedge(i, g.nx) * hedge(k, g.nz) : 0.0) +
-                (k > 0 ? hedge(i, g.nx) * hedge(j, g.ny) : 0.0) + (k < g.nz - 1 ? hedge(i, g.nx) * hedge(j, g.ny) : 0.0);
-        } else {
-            d = L.diag[n];
-            if (d == 0.0) {
-                L.x0[n] = 0.0;
-                continue;
-            }
-        }
-        L.x0[n] = kOmega * L.b[n] / d;
-    }
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= L.n) return;
+    double d = L.diag[n];
+    L.x0[n] = d == 0.0 ? 0.0 : kOmega * L.b[n] / d;
 }
 
-// One damped Jacobi sweep xo = xi + omega D^-1 (b - A xi), optionally adding
-// the prolonged coarse correction alpha_c P xc to xi first (the correction is
-// applied on the fly to every value read, so no separate pass is needed).
-// With last != 0 (finest level) the partials of r.z are written.
-__global__ __launch_bounds__(kBlock) void k_mg_jacobi(MgArgs a, MgLevel L, int level, const double* __restrict__ xi,
+// One damped Jacobi sweep on a coarse level, xo = xi + omega D^-1 (b - A xi),
+// optionally adding the prolonged coarse correction alpha_c P xc to xi first
+// (applied to every value read, so no separate pass is needed).
+__global__ __launch_bounds__(kBlock) void k_mg_jacobi(MgArgs a, MgLevel L, const double* __restrict__ xi,
                                                        double* __restrict__ xo, const double* __restrict__ xc,
-                                                       MgLevel C, double alpha_c, int last) {
+                                                       MgLevel C, double alpha_c) {
     DevState* s = a.s;
     if (s->done) return;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    double rz = 0.0;
-    NodeWalk wk((int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int)stride, L.nx, L.ny);
-    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < L.n; n += stride, wk.advance()) {
-        int i = wk.i, j = wk.j, k = wk.k;
-        double d, Ax, xn;
-        auto val = [&](int64_t m, int ii, int jj, int kk) -> double {
-            double v = xi[m];
-            if (xc) v += alpha_c * xc[((int64_t)(kk / 2) * C.ny + jj / 2) * C.nx + ii / 2];
-            return v;
-        };
-        int64_t pl = (int64_t)L.nx * L.ny;
-        if (level == 0) {
-            if (a.type[n] != 0) {
-                xo[n] = 0.0;
-                continue;
-            }
-            const Grid& g = a.g;
-            double fx = hedge(j, g.ny) * hedge(k, g.nz), fy = hedge(i, g.nx) * hedge(k, g.nz),
-                   fz = hedge(i, g.nx) * hedge(j, g.ny);
-            xn = val(n, i, j, k);
-            double acc = 0.0;
-            d = 0.0;
-            int64_t nb[6] = {n - 1, n + 1, n - L.nx, n + L.nx, n - pl, n + pl};
-            int ni[6] = {i - 1, i + 1, i, i, i, i}, nj[6] = {j, j, j - 1, j + 1, j, j}, nk[6] = {k, k, k, k, k - 1, k + 1};
-            bool has[6] = {i > 0, i < L.nx - 1, j > 0, j < L.ny - 1, k > 0, k < L.nz - 1};
-            double f[6] = {fx, fx, fy, fy, fz, fz};
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= L.n) return;
+    int i = (int)(n % L.nx), j = (int)((n / L.nx) % L.ny), k = (int)(n / ((int64_t)L.nx * L.ny));
+    double d = L.diag[n];
+    if (d == 0.0) {
+        xo[n] = 0.0;
+        return;
+    }
+    auto val = [&](int64_t m, int ii, int jj, int kk) -> double {
+        double v = xi[m];
+        if (xc) v += alpha_c * xc[((int64_t)(kk / 2) * C.ny + jj / 2) * C.nx + ii / 2];
+        return v;
+    };
+    int64_t pl = (int64_t)L.nx * L.ny;
+    // neighbours outside the grid are read at the node itself, zero coefficient
+    const int iw = i > 0 ? i - 1 : i, ie = i < L.nx - 1 ? i + 1 : i;
+    const int js = j > 0 ? j - 1 : j, jn = j < L.ny - 1 ? j + 1 : j;
+    const int kb = k > 0 ? k - 1 : k, kt = k < L.nz - 1 ? k + 1 : k;
+    const int64_t ow = iw - i, oe = ie - i, os = (int64_t)(js - j) * L.nx, on = (int64_t)(jn - j) * L.nx;
+    const int64_t ob = (int64_t)(kb - k) * pl, ot = (int64_t)(kt - k) * pl;
+    const double cw = L.cx[n + ow], ce = L.cx[n], cs = L.cy[n + os], cn = L.cy[n], cb = L.cz[n + ob], ct = L.cz[n];
+    const double xn = val(n, i, j, k);
+    const double xw = val(n + ow, iw, j, k), xe = val(n + oe, ie, j, k), xs = val(n + os, i, js, k),
+                 xnn = val(n + on, i, jn, k), xb = val(n + ob, i, j, kb), xt = val(n + ot, i, j, kt);
+    double sacc = d * xn;
+    sacc += (i > 0 ? cw : 0.0) * xw;
+    sacc += (i < L.nx - 1 ? ce : 0.0) * xe;
+    sacc += (j > 0 ? cs : 0.0) * xs;
+    sacc += (j < L.ny - 1 ? cn : 0.0) * xnn;
+    sacc += (k > 0 ? cb : 0.0) * xb;
+    sacc += (k < L.nz - 1 ? ct : 0.0) * xt;
+    xo[n] = xn + kOmega * (L.b[n] - sacc) / d;
+}
+
+// b_c = P^T (b - A x) between two coarse levels: each coarse node sums the
+// residuals of its children.
+__global__ __launch_bounds__(kBlock) void k_mg_restrict(MgArgs a, MgLevel F, const double* __restrict__ x, MgLevel C) {
+    if (a.s->done) return;
+    int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= C.n) return;
+    int Ix = (int)(I % C.nx), Iy = (int)((I / C.nx) % C.ny), Iz = (int)(I / ((int64_t)C.nx * C.ny));
+    double sum = 0.0;
 #pragma unroll
-            for (int q = 0; q < 6; ++q) {
-                if (!has[q]) continue;
-                d += f[q];
-                // the coarse correction reaches free nodes only; without it the
-                // iterate is already zero on fixed nodes
-                double xj = xc ? (a.type[nb[q]] == 0 ? val(nb[q], ni[q], nj[q], nk[q]) : 0.0) : xi[nb[q]];
-                acc += f[q] * (xn - xj);
-            }
-            Ax = acc;
-        } else {
-            d = L.diag[n];
-            if (d == 0.0) {
-                xo[n] = 0.0;
-                continue;
-            }
-            xn = val(n, i, j, k);
-            double sacc = d * xn;
-            if (i > 0) sacc += L.cx[n - 1] * val(n - 1, i - 1, j, k);
-            if (i < L.nx - 1) sacc += L.cx[n] * val(n + 1, i + 1, j, k);
-            if (j > 0) sacc += L.cy[n - L.nx] * val(n - L.nx, i, j - 1, k);
-            if (j < L.ny - 1) sacc += L.cy[n] * val(n + L.nx, i, j + 1, k);
-            if (k > 0) sacc += L.cz[n - pl] * val(n - pl, i, j, k - 1);
-            if (k < L.nz - 1) sacc += L.cz[n] * val(n + pl, i, j, k + 1);
-            Ax = sacc;
+    for (int t = 0; t < 8; ++t) {
+        int i = 2 * Ix + (t & 1), j = 2 * Iy + ((t >> 1) & 1), k = 2 * Iz + ((t >> 2) & 1);
+        const bool in = i < F.nx && j < F.ny && k < F.nz;
+        // a child outside the grid is evaluated at the first child, weight zero
+        if (!in) {
+            i = 2 * Ix;
+            j = 2 * Iy;
+            k = 2 * Iz;
         }
-        double bn = L.b[n];
-        double xnew = xn + kOmega * (bn - Ax) / d;
-        xo[n] = xnew;
-        if (last) rz += bn * xnew;
+        int64_t n = ((int64_t)k * F.ny + j) * F.nx + i;
+        const double r = F.b[n] - apply_coarse(F, x, n, i, j, k, x[n]);
+        sum += (in && F.diag[n] != 0.0) ? r : 0.0;
     }
-    if (last) {
+    C.b[I] = sum;
+}
+
+// Coarsest level: x = A^-1 b with the stored inverse, one wavefront per row.
+__global__ __launch_bounds__(kBlock) void k_mg_coarsest(MgArgs a, MgLevel L, const double* __restrict__ inv) {
+    if (a.s->done) return;
+    int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    int lane = threadIdx.x & 63;
+    if (row >= L.n) return;
+    double acc = 0.0;
+    for (int64_t c = lane; c < L.n; c += 64) acc += inv[row * L.n + c] * L.b[c];
+    acc = wave_sum(acc);
+    if (lane == 0) L.x0[row] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Finest level (z-marching, see ZMarch)
+
+__device__ inline double fine_diag(const Grid& g, int i, int j, int k) {
+    double hx = hedge(i, g.nx), hy = hedge(j, g.ny), hz = hedge(k, g.nz);
+    double fx = hy * hz, fy = hx * hz, fz = hx * hy;
+    return (i > 0 ? fx : 0.0) + (i < g.nx - 1 ? fx : 0.0) + (j > 0 ? fy : 0.0) + (j < g.ny - 1 ? fy : 0.0) +
+           (k > 0 ? fz : 0.0) + (k < g.nz - 1 ? fz : 0.0);
+}
+
+// Input value of a fine sweep at node m = (i, j, k):
+//   kFineFirst: the first sweep from zero, omega b / D (b is zero on fixed nodes);
+//   kFineCorr : xi + alpha_c P xc on free nodes, zero on fixed nodes;
+//   kFinePlain: xi (zero on fixed nodes).
+// The diagonal of a free node does not depend on k (free nodes are never on
+// a z face), so kFineFirst takes omega / D of the node's column, cw.
+constexpr int kFinePlain = 0, kFineFirst = 1, kFineCorr = 2;
+
+template <int MODE>
+struct FineIn {
+    const uint8_t* __restrict__ type;
+    const double* __restrict__ xi;
+    const double* __restrict__ b;
+    const double* __restrict__ xc;
+    int cnx, cny;
+    double ac;
+    __device__ double operator()(int64_t m, int i, int j, int k, double cw) const {
+        if (MODE == kFineFirst) return cw * b[m];
+        if (MODE == kFineCorr) {
+            // all three loads unconditional and the mask applied by a product
+            // (a select lets the compiler branch around the loads)
+            const uint8_t tv = type[m];
+            const double xv = xi[m];
+            const double cv = xc[((int64_t)(k >> 1) * cny + (j >> 1)) * cnx + (i >> 1)];
+            return (xv + ac * cv) * (double)(tv == 0);
+        }
+        return xi[m];
+    }
+};
+
+// omega / D for a free node of column (i, j) (zero outside the grid)
+__device__ inline double col_weight(const Grid& g, int i, int j) {
+    if (i < 0 || i >= g.nx || j < 0 || j >= g.ny) return 0.0;
+    return kOmega / fine_diag(g, i, j, 1 < g.nz - 1 ? 1 : 0);
+}
+
+// One damped Jacobi sweep on the finest level; with LAST the partials of
+// r.z (b . xo) are written, one per block.
+template <int MODE, bool LAST>
+__global__ __launch_bounds__(kBlock) void k_mg_fine_sweep(MgArgs a, MgLevel L, const double* __restrict__ xi,
+                                                           double* __restrict__ xo, const double* __restrict__ xc,
+                                                           MgLevel C, double alpha_c, int kc) {
+    DevState* s = a.s;
+    if (s->done) return;
+    const Grid& g = a.g;
+    FineIn<MODE> in{a.type, xi, L.b, xc, C.nx, C.ny, alpha_c};
+    ZMarch t = zmarch(g.nx, g.ny, g.nz, kc);
+    double rz = 0.0;
+    if (t.col) {
+        int i = t.i, j = t.j;
+        int64_t pl = (int64_t)g.nx * g.ny;
+        int64_t n = (int64_t)t.k0 * pl + (int64_t)j * g.nx + i;
+        double hx = hedge(i, g.nx), hy = hedge(j, g.ny), fz = hx * hy;
+        double cw = col_weight(g, i, j), cwW = 0.0, cwE = 0.0, cwS = 0.0, cwN = 0.0;
+        if (MODE == kFineFirst) {
+            cwW = col_weight(g, i - 1, j);
+            cwE = col_weight(g, i + 1, j);
+            cwS = col_weight(g, i, j - 1);
+            cwN = col_weight(g, i, j + 1);
+        }
+        // neighbours outside the grid are read at the node itself (every load
+        // is unconditional, so a step's loads are issued together) and given
+        // a zero weight
+        const int iw = i > 0 ? i - 1 : i, ie = i < g.nx - 1 ? i + 1 : i;
+        const int js = j > 0 ? j - 1 : j, jn = j < g.ny - 1 ? j + 1 : j;
+        const int64_t ow = iw - i, oe = ie - i, os = (int64_t)(js - j) * g.nx, on = (int64_t)(jn - j) * g.nx;
+        const double ww = i > 0 ? hy : 0.0, we = i < g.nx - 1 ? hy : 0.0;
+        const double ws = j > 0 ? hx : 0.0, wn = j < g.ny - 1 ? hx : 0.0;
+        double vm = in(t.k0 > 0 ? n - pl : n, i, j, t.k0 > 0 ? t.k0 - 1 : t.k0, cw);
+        if (t.k0 == 0) vm = 0.0;
+        double vc = in(n, i, j, t.k0, cw);
+        for (int k = t.k0; k < t.k1; ++k, n += pl) {
+            const bool up = k + 1 < g.nz;
+            double vp = in(up ? n + pl : n, i, j, up ? k + 1 : k, cw);
+            if (!up) vp = 0.0;
+            const double xw = in(n + ow, iw, j, k, cwW), xe = in(n + oe, ie, j, k, cwE);
+            const double xs = in(n + os, i, js, k, cwS), xn = in(n + on, i, jn, k, cwN);
+            const double bn = L.b[n];
+            const bool fr = a.type[n] == 0;
+            // a free node is never on a z face: fx = hy, fy = hx (hz = 1)
+            double acc = 0.0;
+            acc += ww * (vc - xw);
+            acc += we * (vc - xe);
+            acc += ws * (vc - xs);
+            acc += wn * (vc - xn);
+            acc += fz * (vc - vm);
+            acc += fz * (vc - vp);
+            const double out = (vc + cw * (bn - acc)) * (double)fr;  // values are finite
+            if (LAST) rz += bn * out;
+            xo[n] = out;
+            vm = vc;
+            vc = vp;
+        }
+    }
+    if (LAST) {
         __shared__ double sh[kBlock / 64];
-        double t = block_sum(rz, sh);
-        if (threadIdx.x == 0) a.part_rz[blockIdx.x] = t;
+        double tsum = block_sum(rz, sh);
+        if (threadIdx.x == 0) a.part_rz[blockIdx.x] = tsum;
     }
 }
 
-// b_c = P^T (b - A x): each coarse node sums the residuals of its children.
-__global__ __launch_bounds__(kBlock) void k_mg_restrict(MgArgs a, MgLevel F, int level, const double* __restrict__ x,
-                                                         MgLevel C) {
+// b_1 = P^T (b - A x) from the finest level (kc even, so both fine planes of
+// a coarse plane are in one block). The residuals of the two planes are added
+// in the thread, the x pair by a lane exchange and the y pair through LDS,
+// always as (even + odd).
+__global__ __launch_bounds__(kBlock) void k_mg_fine_restrict(MgArgs a, MgLevel L, const double* __restrict__ x,
+                                                              MgLevel C, int kc) {
     if (a.s->done) return;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    NodeWalk wk((int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int)stride, C.nx, C.ny);
-    for (int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; I < C.n; I += stride, wk.advance()) {
-        int Ix = wk.i, Iy = wk.j, Iz = wk.k;
-        double sum = 0.0;
-        for (int t = 0; t < 8; ++t) {
-            int i = 2 * Ix + (t & 1), j = 2 * Iy + ((t >> 1) & 1), k = 2 * Iz + ((t >> 2) & 1);
-            if (i >= F.nx || j >= F.ny || k >= F.nz) continue;
-            int64_t n = ((int64_t)k * F.ny + j) * F.nx + i;
-            double Ax;
-            if (level == 0) {
-                if (a.type[n] != 0) continue;
-                double d;
-                Ax = apply_fine(a.g, a.type, x, n, i, j, k, x[n], &d);
-            } else {
-                if (F.diag[n] == 0.0) continue;
-                Ax = apply_coarse(F, x, n, i, j, k, x[n]);
-            }
-            sum += F.b[n] - Ax;
+    __shared__ double sh[4][64];
+    const Grid& g = a.g;
+    ZMarch t = zmarch(g.nx, g.ny, g.nz, kc);
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int i = t.i, j = t.j;
+    const bool col = t.col;
+    const int64_t pl = (int64_t)g.nx * g.ny;
+    int64_t n = col ? (int64_t)t.k0 * pl + (int64_t)j * g.nx + i : 0;
+    double hx = hedge(i, g.nx), hy = hedge(j, g.ny), fz = hx * hy;
+    const int iw = i > 0 ? i - 1 : i, ie = i < g.nx - 1 ? i + 1 : i;
+    const int js = j > 0 ? j - 1 : j, jn = j < g.ny - 1 ? j + 1 : j;
+    const int64_t ow = iw - i, oe = ie - i, os = (int64_t)(js - j) * g.nx, on = (int64_t)(jn - j) * g.nx;
+    const double ww = i > 0 ? hy : 0.0, we = i < g.nx - 1 ? hy : 0.0;
+    const double ws = j > 0 ? hx : 0.0, wn = j < g.ny - 1 ? hx : 0.0;
+    double vm = (col && t.k0 > 0) ? x[n - pl] : 0.0;
+    double vc = col ? x[n] : 0.0;
+    double pair = 0.0;
+    for (int k = t.k0; k < t.k1; ++k, n += pl) {
+        double res = 0.0;
+        double vp = 0.0;
+        if (col) {
+            const bool up = k + 1 < g.nz;
+            vp = x[up ? n + pl : n];
+            if (!up) vp = 0.0;
+            const double xw = x[n + ow], xe = x[n + oe], xs = x[n + os], xn = x[n + on];
+            const double bn = L.b[n];
+            const bool fr = a.type[n] == 0;
+            double acc = 0.0;
+            acc += ww * (vc - xw);
+            acc += we * (vc - xe);
+            acc += ws * (vc - xs);
+            acc += wn * (vc - xn);
+            acc += fz * (vc - vm);
+            acc += fz * (vc - vp);
+            res = fr ? bn - acc : 0.0;
         }
-        C.b[I] = sum;
-    }
-}
-
-// Coarsest level: kCoarseSweeps damped Jacobi sweeps from zero in one block.
-__global__ __launch_bounds__(1024) void k_mg_coarsest(MgArgs a, MgLevel L) {
-    if (a.s->done) return;
-    __shared__ double xs[2][1024];
-    int64_t n = threadIdx.x;
-    bool act = n < L.n && L.diag[n] != 0.0;
-    double bn = n < L.n ? L.b[n] : 0.0;
-    double d = act ? L.diag[n] : 1.0;
-    xs[0][threadIdx.x] = 0.0;
-    __syncthreads();
-    for (int it = 0; it < kCoarseSweeps; ++it) {
-        const double* xi = xs[it & 1];
-        double* xo = xs[(it + 1) & 1];
-        if (n < L.n) {
-            double v = 0.0;
-            if (act) {
-                int ci = (int)(n % L.nx), cj = (int)((n / L.nx) % L.ny), ck = (int)(n / ((int64_t)L.nx * L.ny));
-                double Ax = apply_coarse(L, xi, n, ci, cj, ck, xi[n]);
-                v = xi[n] + kOmega * (bn - Ax) / d;
+        pair += res;
+        if ((k & 1) || k == g.nz - 1) {
+            double o = __shfl_xor(pair, 1);
+            double sx = (tx & 1) ? o + pair : pair + o;
+            sh[ty][tx] = sx;
+            __syncthreads();
+            if (!(tx & 1) && !(ty & 1) && col) {
+                int64_t I = ((int64_t)(k >> 1) * C.ny + (j >> 1)) * C.nx + (i >> 1);
+                C.b[I] = sh[ty][tx] + sh[ty + 1][tx];
             }
-            xo[n] = v;
+            __syncthreads();
+            pair = 0.0;
         }
-        __syncthreads();
+        vm = vc;
+        vc = vp;
     }
-    if (n < L.n) L.x0[n] = xs[kCoarseSweeps & 1][n];
 }
 
 // ---------------------------------------------------------------------------
 // Host side
 
-// One node per thread, except for the kernel that writes partial sums (a
-// fixed number of blocks, as many as the CG kernels read).
-static unsigned mg_grid(int64_t n, bool partials) {
-    if (partials) return kMgBlocks;
+static unsigned mg_grid(int64_t n) {
     int64_t g = (n + kBlock - 1) / kBlock;
     return (unsigned)(g < 1 ? 1 : g);
+}
+
+// Inverse of the coarsest operator (n <= 1024) by Cholesky factorization on
+// the host; rows and columns of nodes without unknowns (diag 0) stay zero.
+static int coarsest_inverse(const MgLevel& L, const std::vector<double>& dg, const std::vector<double>& cx,
+                            const std::vector<double>& cy, const std::vector<double>& cz, std::vector<double>& inv) {
+    const int64_t n = L.n;
+    std::vector<int> act;
+    std::vector<int> pos(n, -1);
+    for (int64_t I = 0; I < n; ++I)
+        if (dg[I] != 0.0) {
+            pos[I] = (int)act.size();
+            act.push_back((int)I);
+        }
+    const int m = (int)act.size();
+    std::vector<double> A((size_t)m * m, 0.0);
+    const int64_t pl = (int64_t)L.nx * L.ny;
+    for (int r = 0; r < m; ++r) {
+        int64_t I = act[r];
+        int i = (int)(I % L.nx), j = (int)((I / L.nx) % L.ny), k = (int)(I / pl);
+        A[(size_t)r * m + r] = dg[I];
+        auto couple = [&](int64_t J, double v) {
+            if (J < 0 || J >= n || pos[J] < 0 || v == 0.0) return;
+            A[(size_t)r * m + pos[J]] = v;
+        };
+        if (i > 0) couple(I - 1, cx[I - 1]);
+        if (i < L.nx - 1) couple(I + 1, cx[I]);
+        if (j > 0) couple(I - L.nx, cy[I - L.nx]);
+        if (j < L.ny - 1) couple(I + L.nx, cy[I]);
+        if (k > 0) couple(I - pl, cz[I - pl]);
+        if (k < L.nz - 1) couple(I + pl, cz[I]);
+    }
+    // A = R^T R (upper R in place)
+    for (int c = 0; c < m; ++c) {
+        double d = A[(size_t)c * m + c];
+        for (int t = 0; t < c; ++t) d -= A[(size_t)t * m + c] * A[(size_t)t * m + c];
+        if (!(d > 0.0)) return -3;
+        d = std::sqrt(d);
+        A[(size_t)c * m + c] = d;
+        for (int col = c + 1; col < m; ++col) {
+            double v = A[(size_t)c * m + col];
+            for (int t = 0; t < c; ++t) v -= A[(size_t)t * m + c] * A[(size_t)t * m + col];
+            A[(size_t)c * m + col] = v / d;
+        }
+    }
+    inv.assign((size_t)n * n, 0.0);
+    std::vector<double> y(m);
+    for (int e = 0; e < m; ++e) {
+        // R^T y = e_e, then R x = y
+        for (int r = 0; r < m; ++r) {
+            double v = (r == e) ? 1.0 : 0.0;
+            for (int t = 0; t < r; ++t) v -= A[(size_t)t * m + r] * y[t];
+            y[r] = v / A[(size_t)r * m + r];
+        }
+        for (int r = m - 1; r >= 0; --r) {
+            double v = y[r];
+            for (int t = r + 1; t < m; ++t) v -= A[(size_t)r * m + t] * y[t];
+            y[r] = v / A[(size_t)r * m + r];
+        }
+        for (int r = 0; r < m; ++r) inv[(size_t)act[r] * n + act[e]] = y[r];
+    }
+    return 0;
 }
 
 int mg_setup(pic_ctx* c) {
@@ -398,6 +542,10 @@ int mg_setup(pic_ctx* c) {
     MgHier* h = new MgHier();
     h->nlev = (int)dims.size();
     int64_t nn = c->g.nn;
+    if (h->nlev < 2 || (int64_t)dims.back().x * dims.back().y * dims.back().z > 1024) {
+        delete h;
+        return -3;
+    }
     h->z[0] = (double*)take(nn * 8);
     h->z[1] = (double*)take(nn * 8);
     h->part = (double*)take(64 * kMgBlocks * 8);
@@ -422,6 +570,8 @@ int mg_setup(pic_ctx* c) {
         L.x1 = (double*)take(L.n * 8);
         L.b = (double*)take(L.n * 8);
     }
+    MgLevel& Lc = h->lv[h->nlev - 1];
+    h->cinv = (double*)take((size_t)Lc.n * Lc.n * 8);
     // two Jacobi sweeps each way; the piecewise-constant prolongation leaves
     // the coarse correction too small by about a factor 2, which the weight
     // alpha_c = 2 restores (24 instead of 60 iterations to 1e-8 on the
@@ -429,6 +579,12 @@ int mg_setup(pic_ctx* c) {
     h->pre = 2;
     h->post = 2;
     h->alpha_c = 2.0;
+    h->zm_blocks = zmarch_grid(c->g.nx, c->g.ny, c->g.nz, kMgBlocks, 1, &h->zm_kc);
+    h->zr_blocks = zmarch_grid(c->g.nx, c->g.ny, c->g.nz, kMgBlocks, 2, &h->zr_kc);
+    if (h->zm_blocks > 2048) {
+        delete h;
+        return -3;
+    }
     for (int l = 1; l < h->nlev; ++l) {
         MgLevel& C = h->lv[l];
         unsigned G = (unsigned)((C.n + kBlock - 1) / kBlock);
@@ -437,18 +593,36 @@ int mg_setup(pic_ctx* c) {
         else
             hipLaunchKernelGGL(k_mg_build, dim3(G), dim3(kBlock), 0, c->stream, h->lv[l - 1], C);
     }
-    if (h->lv[h->nlev - 1].n > 1024) {
+    // exact solve on the coarsest level
+    int64_t m = Lc.n;
+    std::vector<double> dg(m), cx(m), cy(m), cz(m), inv;
+    if (hipMemcpyAsync(dg.data(), Lc.diag, m * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipMemcpyAsync(cx.data(), Lc.cx, m * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipMemcpyAsync(cy.data(), Lc.cy, m * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipMemcpyAsync(cz.data(), Lc.cz, m * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        delete h;
+        return -2;
+    }
+    if (coarsest_inverse(Lc, dg, cx, cy, cz, inv) != 0) {
         delete h;
         return -3;
+    }
+    if (hipMemcpyAsync(h->cinv, inv.data(), inv.size() * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        delete h;
+        return -2;
     }
     c->mg_host = h;
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-// z = V-cycle(r) on the finest level; returns the buffer holding z. The
-// first kernel finishes r.r and tests convergence, the last writes the
-// partials of r.z.
-double* mg_vcycle(pic_ctx* c, double* part_rr, double* part_bb, double* part_rz, int cg_blocks) {
+// z = V-cycle(r) on the finest level; returns the buffer holding z and, in
+// n_rz, the number of r.z partials written. The first kernel finishes r.r
+// and tests convergence, the last writes the partials of r.z. Every call
+// launches the same kernels with the same arguments.
+double* mg_vcycle(pic_ctx* c, double* part_rr, double* part_bb, double* part_rz, int cg_blocks, int* n_rz,
+                  bool timed) {
     MgHier* h = (MgHier*)c->mg_host;
     MgArgs a;
     a.g = c->g;
@@ -457,42 +631,62 @@ double* mg_vcycle(pic_ctx* c, double* part_rr, double* part_bb, double* part_rz,
     a.part_rr = part_rr;
     a.part_bb = part_bb;
     a.part_rz = part_rz;
-    int nl = h->nlev;
-    // descending: pre-smoothing and restriction
+    const int nl = h->nlev;
+    const double* nul = nullptr;
+    double* pre_out[kMgMaxLevels];  // pre-smoothed iterate per level
+    double* res[kMgMaxLevels];      // final iterate per level
+    hipLaunchKernelGGL(k_mg_test, dim3(1), dim3(kBlock), 0, c->stream, a, cg_blocks);
+    // descending: pre-smoothing (first sweep from zero + one sweep) and restriction
     for (int l = 0; l < nl - 1; ++l) {
         MgLevel& L = h->lv[l];
-        if (l == 0) hipLaunchKernelGGL(k_mg_test, dim3(1), dim3(kBlock), 0, c->stream, a, cg_blocks);
-        hipLaunchKernelGGL(k_mg_first, dim3(mg_grid(L.n, false)), dim3(kBlock), 0, c->stream, a, L, l);
-        double* xi = L.x0;
-        double* xo = L.x1;
-        for (int s = 1; s < h->pre; ++s) {
-            hipLaunchKernelGGL(k_mg_jacobi, dim3(mg_grid(L.n, false)), dim3(kBlock), 0, c->stream, a, L, l, xi, xo,
-                               (const double*)nullptr, h->lv[l + 1], 0.0, 0);
-            std::swap(xi, xo);
+        MgLevel& C = h->lv[l + 1];
+        if (l == 0) {
+            int t1 = timed ? tic(c, PIC_T_MG_FIRST) : -1;
+            hipLaunchKernelGGL((k_mg_fine_sweep<kFineFirst, false>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream, a,
+                               L, nul, L.x0, nul, C, 0.0, h->zm_kc);
+            toc(c, t1);
+            int t2 = timed ? tic(c, PIC_T_MG_RESTRICT) : -1;
+            hipLaunchKernelGGL(k_mg_fine_restrict, dim3(h->zr_blocks), dim3(kBlock), 0, c->stream, a, L,
+                               (const double*)L.x0, C, h->zr_kc);
+            toc(c, t2);
+            pre_out[0] = L.x0;
+        } else {
+            hipLaunchKernelGGL(k_mg_first, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L);
+            hipLaunchKernelGGL(k_mg_jacobi, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L, (const double*)L.x0,
+                               L.x1, nul, C, 0.0);
+            hipLaunchKernelGGL(k_mg_restrict, dim3(mg_grid(C.n)), dim3(kBlock), 0, c->stream, a, L, (const double*)L.x1,
+                               C);
+            pre_out[l] = L.x1;
         }
-        // the pre-smoothed iterate must sit in x0 for the way up
-        if (xi != L.x0) std::swap(L.x0, L.x1);
-        hipLaunchKernelGGL(k_mg_restrict, dim3(mg_grid(h->lv[l + 1].n, false)), dim3(kBlock), 0, c->stream, a, L, l, L.x0,
-                           h->lv[l + 1]);
     }
-    hipLaunchKernelGGL(k_mg_coarsest, dim3(1), dim3(1024), 0, c->stream, a, h->lv[nl - 1]);
-    // ascending: correction (fused into the first post sweep) and smoothing
-    double* out = nullptr;
+    hipLaunchKernelGGL(k_mg_coarsest, dim3((unsigned)((h->lv[nl - 1].n + 3) / 4)), dim3(kBlock), 0, c->stream, a,
+                       h->lv[nl - 1], (const double*)h->cinv);
+    res[nl - 1] = h->lv[nl - 1].x0;
+    // ascending: correction (fused into the first post sweep) and one more sweep
     for (int l = nl - 2; l >= 0; --l) {
         MgLevel& L = h->lv[l];
-        double* xi = L.x0;
-        double* xo = L.x1;
-        for (int s = 0; s < h->post; ++s) {
-            bool last = (l == 0) && (s == h->post - 1);
-            hipLaunchKernelGGL(k_mg_jacobi, dim3(mg_grid(L.n, last)), dim3(kBlock), 0, c->stream, a, L, l, xi, xo,
-                               s == 0 ? (const double*)h->lv[l + 1].x0 : (const double*)nullptr, h->lv[l + 1],
-                               h->alpha_c, last ? 1 : 0);
-            std::swap(xi, xo);
+        MgLevel& C = h->lv[l + 1];
+        double* xi = pre_out[l];
+        double* xo = xi == L.x0 ? L.x1 : L.x0;
+        if (l == 0) {
+            int t1 = timed ? tic(c, PIC_T_MG_CORR) : -1;
+            hipLaunchKernelGGL((k_mg_fine_sweep<kFineCorr, false>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream, a,
+                               L, (const double*)xi, xo, (const double*)res[1], C, h->alpha_c, h->zm_kc);
+            toc(c, t1);
+            int t2 = timed ? tic(c, PIC_T_MG_LAST) : -1;
+            hipLaunchKernelGGL((k_mg_fine_sweep<kFinePlain, true>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream, a,
+                               L, (const double*)xo, xi, nul, C, 0.0, h->zm_kc);
+            toc(c, t2);
+        } else {
+            hipLaunchKernelGGL(k_mg_jacobi, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L, (const double*)xi, xo,
+                               (const double*)res[l + 1], C, h->alpha_c);
+            hipLaunchKernelGGL(k_mg_jacobi, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L, (const double*)xo, xi,
+                               nul, C, 0.0);
         }
-        if (xi != L.x0) std::swap(L.x0, L.x1);
-        out = L.x0;
+        res[l] = xi;
     }
-    return out;
+    *n_rz = (int)h->zm_blocks;
+    return res[0];
 }
 
 void mg_free(pic_ctx* c) {

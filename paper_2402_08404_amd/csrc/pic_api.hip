@@ -89,7 +89,7 @@ size_t pic::scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[
     size_t tsz = cfg->precision == PIC_F32 ? 4 : 8;
     int64_t scan_n = std::max(std::max(nc + 1, 256 * ((capsum + 4095) / 4096 + 1)), std::max(capsum, words));
     int64_t scan_blocks = (scan_n + 4095) / 4096 + 1;
-    int64_t parts = std::max<int64_t>(4 * 1024, 8 * 512) + 64;  // CG/MG partials (4 x 1024), moments (8 x 512)
+    int64_t parts = std::max<int64_t>(4 * 2048, 8 * 512) + 64;  // CG/MG partials (4 x 2048), moments (8 x 512)
     pic_ctx dummy;
     pic_ctx* t = c ? c : &dummy;
     t->st = (DevState*)take(sizeof(DevState));
@@ -480,6 +480,9 @@ void pic_destroy(pic_ctx* c) {
         delete[] c->ev_slot;
     }
     if (c->host_st) (void)hipHostFree(c->host_st);
+    if (c->pcg_exec) (void)hipGraphExecDestroy(c->pcg_exec);
+    if (c->pcg_graph) (void)hipGraphDestroy(c->pcg_graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     mg_free(c);
     delete c;
 }

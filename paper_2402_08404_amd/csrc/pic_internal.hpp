@@ -45,6 +45,7 @@ struct DevState {
     // CG scalars
     double rr, bb, rr0, pq, alpha, beta, rtol;
     double rrbuf[2], rzbuf[2];
+    double rz_prev;                    // r.z of the previous preconditioned iteration
     int it, maxit, done, zero_solution;
     unsigned int red_count;
     // mixed-precision refinement
@@ -173,6 +174,42 @@ __device__ inline int64_t xcd_block(int64_t b, int64_t G) {
     return x * per + (x < rem ? x : rem) + t;
 }
 
+// z-marching tiles for stencils on a node grid: blocks of 64 x 4 threads over
+// (x, y) (block index remapped so that consecutive tiles share an XCD), each
+// thread walking kc consecutive planes of one (x, y) column. Values of the
+// planes below and above are carried in registers, so each step reads one new
+// plane value per array; in-plane neighbours are L1/L2 hits.
+struct ZMarch {
+    int i, j, k0, k1;
+    bool col;  // the column exists (the last x / y tiles may be partial)
+};
+
+__device__ inline ZMarch zmarch(int nx, int ny, int nz, int kc) {
+    int ntx = (nx + 63) >> 6, nty = (ny + 3) >> 2;
+    int64_t b = xcd_block(blockIdx.x, gridDim.x);
+    int bx = (int)(b % ntx);
+    int64_t r = b / ntx;
+    int by = (int)(r % nty), bz = (int)(r / nty);
+    ZMarch z;
+    z.i = bx * 64 + (int)(threadIdx.x & 63);
+    z.j = by * 4 + (int)(threadIdx.x >> 6);
+    z.k0 = bz * kc;
+    z.k1 = z.k0 + kc < nz ? z.k0 + kc : nz;
+    z.col = z.i < nx && z.j < ny;
+    return z;
+}
+
+// Grid of a z-marching launch of about `target` blocks; kc is rounded up to
+// a multiple of `align`.
+inline unsigned zmarch_grid(int nx, int ny, int nz, int target, int align, int* kc) {
+    int64_t cols = (int64_t)((nx + 63) / 64) * ((ny + 3) / 4);
+    int64_t k = (nz * cols + target - 1) / target;
+    if (k < 1) k = 1;
+    k = (k + align - 1) / align * align;
+    *kc = (int)k;
+    return (unsigned)(cols * ((nz + k - 1) / k));
+}
+
 // Node coordinates along a strided walk n, n + step, n + 2 step, ... without
 // divisions: the step is decomposed once in base (ny, nx) and carried.
 struct NodeWalk {
@@ -235,6 +272,30 @@ __device__ inline T block_sum(T v, T* sh) {
     return r;  // valid in thread 0
 }
 
+// Sum of nparts (>= 1) per-block partials in a fixed order, returned to every
+// thread of the block: each thread adds up to 8 strided values per round with
+// the loads issued together (indices clamped, tail masked by a product), then
+// a block reduction. Uses kBlock / 64 + 1 doubles of shared memory.
+__device__ inline double sum_partials_n(const double* __restrict__ part, int nparts) {
+    __shared__ double sh[kBlock / 64];
+    __shared__ double res;
+    double v = 0.0;
+    for (int base = 0; base < nparts; base += 8 * (int)blockDim.x) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            int idx = base + u * (int)blockDim.x + (int)threadIdx.x;
+            t[u] = part[idx < nparts ? idx : nparts - 1] * (double)(idx < nparts);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += t[u];
+    }
+    double tot = block_sum(v, sh);
+    if (threadIdx.x == 0) res = tot;
+    __syncthreads();
+    return res;
+}
+
 }  // namespace pic
 
 // ---------------------------------------------------------------------------
@@ -285,6 +346,11 @@ struct pic_ctx {
     void* mg_host = nullptr;      // multigrid hierarchy (host description)
     void* mixed = nullptr;        // mixed-precision vectors
     struct unet* learned = nullptr;  // network of PIC_GUESS_LEARNED
+    // captured pair of preconditioned CG iterations (built at the first
+    // unprofiled multigrid solve)
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t pcg_graph = nullptr;
+    hipGraphExec_t pcg_exec = nullptr;
     int learn_smooth = 0;            // binomial filter passes on its output
     // host state
     pic::DevState* host_st = nullptr;  // pinned mirror
@@ -318,7 +384,8 @@ int mgcg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess
 int mixed_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess, double rtol, int maxit,
                 pic_solve_info* info);
 size_t mg_bytes(const pic_config* cfg);
-double* mg_vcycle(pic_ctx* c, double* part_rr, double* part_bb, double* part_rz, int cg_blocks);
+double* mg_vcycle(pic_ctx* c, double* part_rr, double* part_bb, double* part_rz, int cg_blocks, int* n_rz,
+                  bool timed);
 void mg_free(pic_ctx* c);
 hipError_t scan_u32(pic_ctx* c, const uint32_t* in, uint32_t* out, int64_t n_max, const uint32_t* nd,
                     uint32_t* total, bool zero_in, bool popcount);

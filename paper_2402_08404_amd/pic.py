@@ -195,7 +195,8 @@ def pic_events(ctx, cap: int) -> list:
     return [(buf[i].kind, buf[i].id_a, buf[i].id_b, buf[i].new_ion, buf[i].new_e) for i in range(m)]
 
 
-TIMERS = ("inject", "push_e", "push", "particles", "collide", "mcc", "solve", "cg_a", "cg_b", "step", "mg", "deposit", "bin")
+TIMERS = ("inject", "push_e", "push", "particles", "collide", "mcc", "solve", "cg_a", "cg_b", "step", "mg", "deposit",
+          "bin", "mg_first", "mg_restrict", "mg_corr", "mg_last")
 
 
 def pic_profile(ctx, enable: bool):
@@ -203,8 +204,8 @@ def pic_profile(ctx, enable: bool):
 
 
 def pic_timers(ctx, reset: bool = True) -> dict:
-    ms = (C.c_double * 13)()
-    cnt = (C.c_int64 * 13)()
+    ms = (C.c_double * len(TIMERS))()
+    cnt = (C.c_int64 * len(TIMERS))()
     _check(lib().pic_timers(ctx, ms, cnt, 1 if reset else 0), ctx)
     return {name: (ms[i], cnt[i]) for i, name in enumerate(TIMERS)}
 
