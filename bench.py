@@ -57,15 +57,16 @@ def push_bytes(n_particles, n_nodes, fp32=True):
     return per_p * n_particles + per_n * n_nodes
 
 
-# Algorithmic bytes per node of the solver kernels on the finest level (FP64
-# vectors, uint8 node type): what each launch must read and write once.
+# Algorithmic bytes per node of the solver kernels on the finest level: FP64
+# Krylov vectors (x, r, p, q), FP32 multigrid vectors (z and the smoother's
+# iterates), uint8 node type; what each launch must read and write once.
 SOLVER_BYTES_PER_NODE = {
-    "cg_a": 33,          # read z, p_old, type; write p_new, q
-    "cg_b": 48,          # read p, x, r, q; write x, r
-    "mg_first": 17,      # read b, type; write x
-    "mg_restrict": 18,   # read x, b, type; write the coarse rhs (1/8 per node)
-    "mg_corr": 26,       # read x, b, type, coarse x (1/8 per node); write x
-    "mg_last": 25,       # read x, b, type; write z
+    "cg_a": 29,           # read z (4), p_old (8), type (1); write p_new (8), q (8)
+    "cg_b": 48,           # read p, x, r, q (32); write x, r (16)
+    "mg_first": 13,       # read b (8), type (1); write x (4)
+    "mg_restrict": 13.5,  # read x (4), b (8), type (1); write the coarse rhs (4 per 8 nodes)
+    "mg_corr": 17.5,      # read x (4), b (8), type (1), coarse x (4 per 8 nodes); write x (4)
+    "mg_last": 17,        # read x (4), b (8), type (1); write z (4)
 }
 
 

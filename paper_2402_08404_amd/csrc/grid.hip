@@ -6,6 +6,8 @@
 // faces: for a free node i, sum_j f_ij (phi_i - phi_j) = q_i / (eps0 h), with
 // f_ij = 1 inside, 1/2 on a lateral face and 1/4 on a lateral edge. The
 // operator is applied matrix-free from the node types.
+#include <algorithm>
+
 #include "pic_internal.hpp"
 
 namespace pic {
@@ -469,23 +471,42 @@ int cg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess, 
 }
 
 // ---------------------------------------------------------------------------
-// CG preconditioned by the multigrid V-cycle (z = M r). Per iteration: the
-// V-cycle (its first kernel finishes r.r and tests convergence, its last
-// writes the partials of r.z), then k_pcg_a (beta from r.z, p = z + beta p,
-// q = A p, partials of p.q) and k_pcg_b (alpha, x and r update, partials of
-// r.r). The iteration count and the previous r.z live on the device, so every
-// iteration launches the same kernels with the same arguments.
+// CG preconditioned by the multigrid V-cycle (z = M r, z in FP32). Per
+// iteration: the V-cycle (its first kernel finishes r.r and tests
+// convergence, its last writes the partials of r.z), then k_pcg_a (beta from
+// r.z, p = z + beta p, q = A p, partials of p.q) and k_pcg_b (alpha, x and r
+// update, partials of r.r). The iteration count and the previous r.z live on
+// the device, so every iteration launches the same kernels with the same
+// arguments. TP is the type of the Krylov vectors x, r, p, q: FP64 for the
+// multigrid-preconditioned solver, FP32 for the inner solves of the
+// mixed-precision one. Dot products are always accumulated in FP64.
+
+template <typename TP>
+struct PcgArgs {
+    Grid g;
+    const uint8_t* type;
+    TP* x;
+    TP* r;
+    const TP* p_old;
+    TP* p_new;
+    TP* q;
+    DevState* s;
+    double* part_pq;
+    double* part_rr;
+    int64_t chunk;
+};
 
 // z-marching: p = z + beta p_old at the node and its six neighbours, q = A p.
-__global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs a, const double* __restrict__ z, const double* part_rz,
+template <typename TP>
+__global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs<TP> a, const float* __restrict__ z, const double* part_rz,
                                                    int n_rz, int kc) {
     DevState* s = a.s;
     if (s->done) return;
     const Grid& g = a.g;
     double rz = sum_partials_n(part_rz, n_rz);
     double beta = s->it == 0 ? 0.0 : rz / s->rz_prev;
-    const double* __restrict__ po = a.p_old;
-    auto pv = [&](int64_t m) { return z[m] + beta * po[m]; };  // zero on fixed nodes
+    const TP* __restrict__ po = a.p_old;
+    auto pv = [&](int64_t m) { return (double)z[m] + beta * (double)po[m]; };  // zero on fixed nodes
     ZMarch t = zmarch(g.nx, g.ny, g.nz, kc);
     double pq = 0.0;
     if (t.col) {
@@ -516,18 +537,21 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(CgArgs a, const double* __rest
             acc += wn * (pc - xn);
             acc += fz * (pc - pm);
             acc += fz * (pc - pp);
-            const double qv = fr ? acc : 0.0;
-            pq += pc * qv;
-            a.p_new[n] = pc;
-            a.q[n] = qv;
+            const TP pn = (TP)pc, qn = (TP)(fr ? acc : 0.0);
+            pq += (double)pn * (double)qn;
+            a.p_new[n] = pn;
+            a.q[n] = qn;
             pm = pc;
             pc = pp;
         }
     }
-    write_partial(pq, a.part_pq);
+    __shared__ double sh[kBlock / 64];
+    double tsum = block_sum(pq, sh);
+    if (threadIdx.x == 0) a.part_pq[blockIdx.x] = tsum;
 }
 
-__global__ __launch_bounds__(kBlock) void k_pcg_b(CgArgs a, const double* part_rz, int n_rz, int n_pq) {
+template <typename TP>
+__global__ __launch_bounds__(kBlock) void k_pcg_b(PcgArgs<TP> a, const double* part_rz, int n_rz, int n_pq) {
     DevState* s = a.s;
     if (s->done) return;
     const Grid& g = a.g;
@@ -541,17 +565,111 @@ __global__ __launch_bounds__(kBlock) void k_pcg_b(CgArgs a, const double* part_r
     // and no node type is needed
     for (int64_t n = b0 + threadIdx.x; n < b1; n += blockDim.x) {
         double p = a.p_new[n];
-        a.x[n] += alpha * p;
-        double r = a.r[n] - alpha * a.q[n];
-        a.r[n] = r;
-        rr += r * r;
+        a.x[n] = (TP)((double)a.x[n] + alpha * p);
+        double r = (double)a.r[n] - alpha * (double)a.q[n];
+        TP rn = (TP)r;
+        a.r[n] = rn;
+        rr += (double)rn * (double)rn;
     }
-    write_partial(rr, a.part_rr);
+    __shared__ double sh[kBlock / 64];
+    double tsum = block_sum(rr, sh);
+    if (threadIdx.x == 0) a.part_rr[blockIdx.x] = tsum;
     // only this block reads or writes the iteration state in this kernel
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         s->rz_prev = rz;
         s->it = s->it + 1;
     }
+}
+
+// Partials of the mixed-precision refinement live after the CG ones.
+constexpr int kPartPq = 0, kPartRr = 2048, kPartBb = 4096, kPartRz = 6144;
+
+// Run the preconditioned iterations on x, r (type TP; r also the V-cycle's
+// right-hand side) after k_cg_setup and the partials of r.r and b.b are in
+// place. p0, p1, q: work vectors of type TP. slot selects the captured graph
+// (0: FP64 solver, 1: inner FP32 solver). Returns 0, or -2 on a HIP error.
+template <typename TP>
+static int pcg_iterate(pic_ctx* c, TP* x, TP* r, TP* p0, TP* p1, TP* q, int maxit, int slot) {
+    const Grid& g = c->g;
+    PcgArgs<TP> a;
+    a.g = g;
+    a.type = c->buf.node_type;
+    a.x = x;
+    a.r = r;
+    a.q = q;
+    a.s = c->st;
+    a.part_pq = c->partials + kPartPq;
+    a.part_rr = c->partials + kPartRr;
+    double* part_bb = c->partials + kPartBb;
+    double* part_rz = c->partials + kPartRz;
+    a.chunk = ((g.nn + kCgBlocks - 1) / kCgBlocks + kBlock - 1) / kBlock * kBlock;
+    int kc = 1;
+    unsigned zb = zmarch_grid(g.nx, g.ny, g.nz, kCgBlocks, 1, &kc);
+    if (zb > 2048) return -3;
+    // one iteration: V-cycle, p update and A p, x and r update
+    auto iteration = [&](TP* p_old, TP* p_new, bool timed) {
+        int tm = timed ? tic(c, PIC_T_MG) : -1;
+        int n_rz = 0;
+        float* z = mg_vcycle<TP>(c, (const TP*)r, a.part_rr, part_bb, part_rz, kCgBlocks, &n_rz, timed);
+        toc(c, tm);
+        a.p_old = p_old;
+        a.p_new = p_new;
+        int ta = timed ? tic(c, PIC_T_CG_A) : -1;
+        hipLaunchKernelGGL(k_pcg_a<TP>, dim3(zb), dim3(kBlock), 0, c->stream, a, (const float*)z,
+                           (const double*)part_rz, n_rz, kc);
+        toc(c, ta);
+        int tb = timed ? tic(c, PIC_T_CG_B) : -1;
+        hipLaunchKernelGGL(k_pcg_b<TP>, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a, (const double*)part_rz, n_rz,
+                           (int)zb);
+        toc(c, tb);
+    };
+    // Without profiling, pairs of iterations run as one captured graph (the
+    // kernels read the iteration state from the device, so every pair is the
+    // same launch sequence; p ping-pongs p0 -> p1 -> p0 within a pair).
+    hipGraph_t& graph = slot ? c->mix_graph : c->pcg_graph;
+    hipGraphExec_t& exec = slot ? c->mix_exec : c->pcg_exec;
+    bool use_graph = !c->prof;
+    if (use_graph && !exec) {
+        bool ok = true;
+        if (!c->cap_stream) ok = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
+        hipStream_t keep = c->stream;
+        if (ok) ok = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            c->stream = c->cap_stream;
+            iteration(p0, p1, false);
+            iteration(p1, p0, false);
+            c->stream = keep;
+            hipGraph_t gr = nullptr;
+            ok = hipStreamEndCapture(c->cap_stream, &gr) == hipSuccess && gr;
+            if (ok) ok = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0) == hipSuccess;
+            if (ok) graph = gr;
+            else if (gr) (void)hipGraphDestroy(gr);
+        }
+        if (!ok) {
+            c->stream = keep;
+            (void)hipGetLastError();
+            return -2;
+        }
+    }
+    // launch in chunks, testing convergence on the host after each; the
+    // first chunk is the iteration count of the previous solve
+    int chunk = c->last_iters[slot] > 2 ? c->last_iters[slot] : 2;
+    int it = 0;
+    while (true) {
+        if (use_graph) {
+            for (int t = 0; t < chunk && it <= maxit; t += 2, it += 2)
+                if (hipGraphLaunch(exec, c->stream) != hipSuccess) return -2;
+        } else {
+            for (int t = 0; t < chunk && it <= maxit; ++t, ++it)
+                iteration((it & 1) ? p1 : p0, (it & 1) ? p0 : p1, it < 64);
+        }
+        (void)hipMemcpyAsync(c->host_st, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream);
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return -2;
+        if (c->host_st->done || it > maxit) break;
+        chunk = 2;
+    }
+    c->last_iters[slot] = c->host_st->it;
+    return 0;
 }
 
 int mgcg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess, double rtol, int maxit,
@@ -571,75 +689,15 @@ int mgcg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess
     a.qscale = ldexp(1.0, -40) * kQe / (kEps0 * g.h);
     a.V0 = V0;
     a.s = c->st;
-    a.part_pq = c->partials;
-    a.part_rr = c->partials + 2048;
-    a.part_bb = c->partials + 4096;
-    double* part_rz = c->partials + 6144;
+    a.part_pq = c->partials + kPartPq;
+    a.part_rr = c->partials + kPartRr;
+    a.part_bb = c->partials + kPartBb;
     a.chunk = ((g.nn + kCgBlocks - 1) / kCgBlocks + kBlock - 1) / kBlock * kBlock;
-    int kc = 1;
-    unsigned zb = zmarch_grid(g.nx, g.ny, g.nz, kCgBlocks, 1, &kc);
-    if (zb > 2048) return -3;
     hipLaunchKernelGGL(k_cg_setup, dim3(1), dim3(1), 0, c->stream, c->st, rtol, maxit);
     hipLaunchKernelGGL(k_cg_init, dim3((unsigned)G), dim3(kBlock), 0, c->stream, a, guess == PIC_GUESS_ZERO);
     hipLaunchKernelGGL(k_cg_resid, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a);
-    // one iteration: V-cycle, p update and A p, x and r update
-    auto iteration = [&](double* p_old, double* p_new, bool timed) {
-        int tm = timed ? tic(c, PIC_T_MG) : -1;
-        int n_rz = 0;
-        double* z = mg_vcycle(c, a.part_rr, a.part_bb, part_rz, kCgBlocks, &n_rz, timed);
-        toc(c, tm);
-        a.p_old = p_old;
-        a.p_new = p_new;
-        int ta = timed ? tic(c, PIC_T_CG_A) : -1;
-        hipLaunchKernelGGL(k_pcg_a, dim3(zb), dim3(kBlock), 0, c->stream, a, (const double*)z, (const double*)part_rz,
-                           n_rz, kc);
-        toc(c, ta);
-        int tb = timed ? tic(c, PIC_T_CG_B) : -1;
-        hipLaunchKernelGGL(k_pcg_b, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a, (const double*)part_rz, n_rz,
-                           (int)zb);
-        toc(c, tb);
-    };
-    // Without profiling, pairs of iterations run as one captured graph (the
-    // kernels read the iteration state from the device, so every pair is
-    // the same launch sequence; p ping-pongs p0 -> p1 -> p0 within a pair).
-    bool use_graph = !c->prof;
-    if (use_graph && !c->pcg_exec) {
-        bool ok = true;
-        if (!c->cap_stream) ok = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
-        hipStream_t keep = c->stream;
-        if (ok) ok = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
-        if (ok) {
-            c->stream = c->cap_stream;
-            iteration(c->cg_p0, c->cg_p1, false);
-            iteration(c->cg_p1, c->cg_p0, false);
-            c->stream = keep;
-            hipGraph_t gr = nullptr;
-            ok = hipStreamEndCapture(c->cap_stream, &gr) == hipSuccess && gr;
-            if (ok) ok = hipGraphInstantiate(&c->pcg_exec, gr, nullptr, nullptr, 0) == hipSuccess;
-            if (ok) c->pcg_graph = gr;
-            else if (gr) (void)hipGraphDestroy(gr);
-        }
-        if (!ok) {
-            c->stream = keep;
-            (void)hipGetLastError();
-            return -2;
-        }
-    }
-    int chunk = 2;
-    int it = 0;
-    while (true) {
-        if (use_graph) {
-            for (int t = 0; t < chunk && it <= maxit; t += 2, it += 2)
-                if (hipGraphLaunch(c->pcg_exec, c->stream) != hipSuccess) return -2;
-        } else {
-            for (int t = 0; t < chunk && it <= maxit; ++t, ++it)
-                iteration((it & 1) ? c->cg_p1 : c->cg_p0, (it & 1) ? c->cg_p0 : c->cg_p1, it < 64);
-        }
-        (void)hipMemcpyAsync(c->host_st, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream);
-        if (hipStreamSynchronize(c->stream) != hipSuccess) return -2;
-        if (c->host_st->done || it > maxit) break;
-        if (chunk < 16) chunk *= 2;
-    }
+    int e = pcg_iterate<double>(c, phi, c->cg_r, c->cg_p0, c->cg_p1, c->cg_q, maxit, 0);
+    if (e) return e;
     hipLaunchKernelGGL(k_cg_zero_free, dim3((unsigned)G), dim3(kBlock), 0, c->stream, g, c->buf.node_type, phi,
                        c->st);
     (void)hipMemcpyAsync(c->host_st, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream);
@@ -651,6 +709,117 @@ int mgcg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess
     info->relres0 = h->zero_solution ? 0.0 : sqrt(h->rr0) / bn;
     info->converged = h->zero_solution || (sqrt(h->rr) <= rtol * bn);
     return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Mixed precision: FP64 residual refinement around FP32 inner solves. Each
+// outer step computes r = b - A phi in FP64 (k_cg_resid), solves A e = r in
+// FP32 (multigrid-preconditioned CG on FP32 vectors, FP64 dot products) to a
+// relative reduction of at most 1e-5, and adds e to phi in FP64.
+
+// r32 = (float) r64, e = 0, p = 0; partials of |r32|^2 as the inner b.b and r.r
+__global__ __launch_bounds__(kBlock) void k_mix_start(Grid g, const double* __restrict__ r64, float* __restrict__ r32,
+                                                       float* __restrict__ e32, float* __restrict__ p32, int64_t chunk,
+                                                       double* part_bb, double* part_rr) {
+    int64_t b0 = xcd_block(blockIdx.x, gridDim.x) * chunk;
+    int64_t b1 = b0 + chunk < g.nn ? b0 + chunk : g.nn;
+    double rr = 0.0;
+    for (int64_t n = b0 + threadIdx.x; n < b1; n += blockDim.x) {
+        float v = (float)r64[n];
+        r32[n] = v;
+        e32[n] = 0.f;
+        p32[n] = 0.f;
+        rr += (double)v * (double)v;
+    }
+    __shared__ double sh[kBlock / 64];
+    double t = block_sum(rr, sh);
+    if (threadIdx.x == 0) {
+        part_bb[blockIdx.x] = t;
+        part_rr[blockIdx.x] = t;
+    }
+}
+
+// phi += e (e is zero on fixed nodes)
+__global__ void k_mix_update(int64_t nn, const float* __restrict__ e32, double* __restrict__ phi) {
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (int64_t)gridDim.x * blockDim.x)
+        phi[n] += (double)e32[n];
+}
+
+__global__ void k_mix_zero_free(Grid g, const uint8_t* type, double* x) {
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < g.nn && type[n] == 0) x[n] = 0.0;
+}
+
+// outer test: FP64 r.r and b.b from the partials of k_cg_resid
+__global__ void k_mix_test(const double* part_rr, const double* part_bb, DevState* s) {
+    double rr = sum_partials_n(part_rr, kCgBlocks);
+    double bb = sum_partials_n(part_bb, kCgBlocks);
+    if (threadIdx.x == 0) {
+        s->rr_outer = rr;
+        s->bb = bb;
+    }
+}
+
+int mixed_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess, double rtol, int maxit,
+                pic_solve_info* info) {
+    if (!c->mg_host) return -3;
+    const Grid& g = c->g;
+    int64_t G = (g.nn + kBlock - 1) / kBlock;
+    CgArgs a;
+    a.g = g;
+    a.type = c->buf.node_type;
+    a.x = phi;
+    a.r = c->cg_r;
+    a.p_old = c->cg_p0;
+    a.p_new = c->cg_p1;
+    a.q = c->cg_q;
+    a.rho = rho;
+    a.qscale = ldexp(1.0, -40) * kQe / (kEps0 * g.h);
+    a.V0 = V0;
+    a.s = c->st;
+    a.part_pq = c->partials + kPartPq;
+    a.part_rr = c->partials + kPartRr;
+    a.part_bb = c->partials + kPartBb;
+    a.chunk = ((g.nn + kCgBlocks - 1) / kCgBlocks + kBlock - 1) / kBlock * kBlock;
+    // FP32 work vectors in the halves of the FP64 CG vectors (r64 stays in cg_r)
+    float* r32 = (float*)c->cg_p0;
+    float* e32 = r32 + g.nn;
+    float* p0 = (float*)c->cg_p1;
+    float* p1 = p0 + g.nn;
+    float* q32 = (float*)c->cg_q;
+    hipLaunchKernelGGL(k_cg_init, dim3((unsigned)G), dim3(kBlock), 0, c->stream, a, guess == PIC_GUESS_ZERO);
+    int total = 0;
+    double bn = 0.0, rn = 0.0, rn0 = -1.0;
+    bool conv = false;
+    for (int outer = 0; outer < 40; ++outer) {
+        hipLaunchKernelGGL(k_cg_resid, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a);
+        hipLaunchKernelGGL(k_mix_test, dim3(1), dim3(kBlock), 0, c->stream, (const double*)a.part_rr,
+                           (const double*)a.part_bb, c->st);
+        (void)hipMemcpyAsync(c->host_st, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream);
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return -2;
+        bn = sqrt(c->host_st->bb);
+        rn = sqrt(c->host_st->rr_outer);
+        if (rn0 < 0) rn0 = rn;
+        conv = bn == 0.0 || rn <= rtol * bn;
+        if (conv || total >= maxit) break;
+        // inner solve to a relative reduction that reaches rtol with a margin,
+        // but not below what FP32 vectors can resolve
+        double inner = std::max(1e-5, 0.5 * rtol * bn / rn);
+        hipLaunchKernelGGL(k_cg_setup, dim3(1), dim3(1), 0, c->stream, c->st, inner, maxit - total);
+        hipLaunchKernelGGL(k_mix_start, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, g, (const double*)c->cg_r, r32,
+                           e32, p0, a.chunk, a.part_bb, a.part_rr);
+        int e = pcg_iterate<float>(c, e32, r32, p0, p1, q32, maxit - total, 1);
+        if (e) return e;
+        total += c->host_st->it;
+        hipLaunchKernelGGL(k_mix_update, dim3(4096), dim3(kBlock), 0, c->stream, g.nn, (const float*)e32, phi);
+    }
+    info->iterations = total;
+    info->relres = bn == 0.0 ? 0.0 : rn / bn;
+    info->relres0 = bn == 0.0 ? 0.0 : rn0 / bn;
+    info->converged = conv;
+    if (bn == 0.0)
+        hipLaunchKernelGGL(k_mix_zero_free, dim3((unsigned)G), dim3(kBlock), 0, c->stream, g, c->buf.node_type, phi);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 // Potential at a point by trilinear interpolation (one thread).

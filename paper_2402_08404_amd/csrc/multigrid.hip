@@ -20,20 +20,26 @@
 namespace pic {
 
 constexpr int kMgMaxLevels = 12;
+
+// Storage of every multigrid vector and coarse operator: FP32 (the V-cycle is
+// a preconditioner, so its precision decides only how good the search
+// directions are; the Krylov vectors, dot products and the convergence test
+// stay FP64). Arithmetic inside the kernels is FP64.
+typedef float mgv;
 constexpr int kMgBlocks = 1024;
 constexpr double kOmega = 6.0 / 7.0;  // damped Jacobi weight for 7-point stencils
 
 struct MgLevel {
     int nx, ny, nz;
     int64_t n;
-    double *diag, *cx, *cy, *cz;  // levels >= 1
-    double *x0, *x1, *b;          // x ping-pong and right-hand side
+    mgv *diag, *cx, *cy, *cz;  // levels >= 1
+    mgv *x0, *x1, *b;          // x ping-pong and right-hand side (b: levels >= 1)
 };
 
 struct MgHier {
     int nlev;
     MgLevel lv[kMgMaxLevels];
-    double* z[2];  // finest-level preconditioned residual (ping-pong)
+    mgv* z[2];     // finest-level preconditioned residual (ping-pong)
     double* part;  // partial sums
     double* cinv;  // inverse of the coarsest operator, n x n (zero rows / columns for fixed nodes)
     int pre, post;
@@ -57,10 +63,10 @@ size_t mg_bytes(const pic_config* cfg) {
     mg_dims(cfg, dims);
     size_t b = 4096 + sizeof(MgHier);
     int64_t nn = (int64_t)cfg->nx * cfg->ny * cfg->nz;
-    b += 2 * nn * 8 + 64 * kMgBlocks * 8;
+    b += 2 * nn * sizeof(mgv) + 2 * 256 + 64 * kMgBlocks * 8;
     for (size_t l = 1; l < dims.size(); ++l) {
         int64_t n = (int64_t)dims[l].x * dims[l].y * dims[l].z;
-        b += 7 * (size_t)n * 8 + 7 * 256;
+        b += 7 * (size_t)n * sizeof(mgv) + 7 * 256;
     }
     int64_t nc = (int64_t)dims.back().x * dims.back().y * dims.back().z;
     if (nc <= 1024) b += (size_t)nc * nc * 8 + 256;
@@ -100,10 +106,10 @@ __global__ void k_mg_build1(Grid g, const uint8_t* __restrict__ type, MgLevel c)
             else if (d == 5 && pk == Iz + 1) cz -= f[d];             // +z face
         }
     }
-    c.diag[I] = dg;
-    c.cx[I] = cx;
-    c.cy[I] = cy;
-    c.cz[I] = cz;
+    c.diag[I] = (mgv)dg;
+    c.cx[I] = (mgv)cx;
+    c.cy[I] = (mgv)cy;
+    c.cz[I] = (mgv)cz;
 }
 
 // Level l+1 from the stored stencil of level l.
@@ -132,10 +138,10 @@ __global__ void k_mg_build(MgLevel f, MgLevel c) {
             else if (d == 5 && pk == Iz + 1) cz += cpl[d];
         }
     }
-    c.diag[I] = dg;
-    c.cx[I] = cx;
-    c.cy[I] = cy;
-    c.cz[I] = cz;
+    c.diag[I] = (mgv)dg;
+    c.cx[I] = (mgv)cx;
+    c.cy[I] = (mgv)cy;
+    c.cz[I] = (mgv)cz;
 }
 
 // ---------------------------------------------------------------------------
@@ -143,7 +149,7 @@ __global__ void k_mg_build(MgLevel f, MgLevel c) {
 
 // (A x)_n on a coarse level. Neighbours outside the grid are read at the node
 // itself with a zero coefficient, so all loads are unconditional.
-__device__ inline double apply_coarse(const MgLevel& L, const double* __restrict__ x, int64_t n, int i, int j, int k,
+__device__ inline double apply_coarse(const MgLevel& L, const mgv* __restrict__ x, int64_t n, int i, int j, int k,
                                       double xn) {
     int64_t pl = (int64_t)L.nx * L.ny;
     const int64_t ow = i > 0 ? -1 : 0, oe = i < L.nx - 1 ? 1 : 0;
@@ -206,15 +212,15 @@ __global__ __launch_bounds__(kBlock) void k_mg_first(MgArgs a, MgLevel L) {
     int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= L.n) return;
     double d = L.diag[n];
-    L.x0[n] = d == 0.0 ? 0.0 : kOmega * L.b[n] / d;
+    L.x0[n] = (mgv)(d == 0.0 ? 0.0 : kOmega * (double)L.b[n] / d);
 }
 
 // One damped Jacobi sweep on a coarse level, xo = xi + omega D^-1 (b - A xi),
 // optionally adding the prolonged coarse correction alpha_c P xc to xi first
 // (applied to every value read, so no separate pass is needed).
-__global__ __launch_bounds__(kBlock) void k_mg_jacobi(MgArgs a, MgLevel L, const double* __restrict__ xi,
-                                                       double* __restrict__ xo, const double* __restrict__ xc,
-                                                       MgLevel C, double alpha_c) {
+__global__ __launch_bounds__(kBlock) void k_mg_jacobi(MgArgs a, MgLevel L, const mgv* __restrict__ xi,
+                                                       mgv* __restrict__ xo, const mgv* __restrict__ xc, MgLevel C,
+                                                       double alpha_c) {
     DevState* s = a.s;
     if (s->done) return;
     int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -222,12 +228,12 @@ __global__ __launch_bounds__(kBlock) void k_mg_jacobi(MgArgs a, MgLevel L, const
     int i = (int)(n % L.nx), j = (int)((n / L.nx) % L.ny), k = (int)(n / ((int64_t)L.nx * L.ny));
     double d = L.diag[n];
     if (d == 0.0) {
-        xo[n] = 0.0;
+        xo[n] = (mgv)0;
         return;
     }
     auto val = [&](int64_t m, int ii, int jj, int kk) -> double {
         double v = xi[m];
-        if (xc) v += alpha_c * xc[((int64_t)(kk / 2) * C.ny + jj / 2) * C.nx + ii / 2];
+        if (xc) v += alpha_c * (double)xc[((int64_t)(kk / 2) * C.ny + jj / 2) * C.nx + ii / 2];
         return v;
     };
     int64_t pl = (int64_t)L.nx * L.ny;
@@ -248,12 +254,12 @@ __global__ __launch_bounds__(kBlock) void k_mg_jacobi(MgArgs a, MgLevel L, const
     sacc += (j < L.ny - 1 ? cn : 0.0) * xnn;
     sacc += (k > 0 ? cb : 0.0) * xb;
     sacc += (k < L.nz - 1 ? ct : 0.0) * xt;
-    xo[n] = xn + kOmega * (L.b[n] - sacc) / d;
+    xo[n] = (mgv)(xn + kOmega * ((double)L.b[n] - sacc) / d);
 }
 
 // b_c = P^T (b - A x) between two coarse levels: each coarse node sums the
 // residuals of its children.
-__global__ __launch_bounds__(kBlock) void k_mg_restrict(MgArgs a, MgLevel F, const double* __restrict__ x, MgLevel C) {
+__global__ __launch_bounds__(kBlock) void k_mg_restrict(MgArgs a, MgLevel F, const mgv* __restrict__ x, MgLevel C) {
     if (a.s->done) return;
     int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (I >= C.n) return;
@@ -270,10 +276,10 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(MgArgs a, MgLevel F, con
             k = 2 * Iz;
         }
         int64_t n = ((int64_t)k * F.ny + j) * F.nx + i;
-        const double r = F.b[n] - apply_coarse(F, x, n, i, j, k, x[n]);
-        sum += (in && F.diag[n] != 0.0) ? r : 0.0;
+        const double r = (double)F.b[n] - apply_coarse(F, x, n, i, j, k, x[n]);
+        sum += (in && F.diag[n] != (mgv)0) ? r : 0.0;
     }
-    C.b[I] = sum;
+    C.b[I] = (mgv)sum;
 }
 
 // Coarsest level: x = A^-1 b with the stored inverse, one wavefront per row.
@@ -283,9 +289,9 @@ __global__ __launch_bounds__(kBlock) void k_mg_coarsest(MgArgs a, MgLevel L, con
     int lane = threadIdx.x & 63;
     if (row >= L.n) return;
     double acc = 0.0;
-    for (int64_t c = lane; c < L.n; c += 64) acc += inv[row * L.n + c] * L.b[c];
+    for (int64_t c = lane; c < L.n; c += 64) acc += inv[row * L.n + c] * (double)L.b[c];
     acc = wave_sum(acc);
-    if (lane == 0) L.x0[row] = acc;
+    if (lane == 0) L.x0[row] = (mgv)acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -306,25 +312,25 @@ __device__ inline double fine_diag(const Grid& g, int i, int j, int k) {
 // a z face), so kFineFirst takes omega / D of the node's column, cw.
 constexpr int kFinePlain = 0, kFineFirst = 1, kFineCorr = 2;
 
-template <int MODE>
+template <int MODE, typename TB>
 struct FineIn {
     const uint8_t* __restrict__ type;
-    const double* __restrict__ xi;
-    const double* __restrict__ b;
-    const double* __restrict__ xc;
+    const mgv* __restrict__ xi;
+    const TB* __restrict__ b;
+    const mgv* __restrict__ xc;
     int cnx, cny;
     double ac;
     __device__ double operator()(int64_t m, int i, int j, int k, double cw) const {
-        if (MODE == kFineFirst) return cw * b[m];
+        if (MODE == kFineFirst) return cw * (double)b[m];
         if (MODE == kFineCorr) {
             // all three loads unconditional and the mask applied by a product
             // (a select lets the compiler branch around the loads)
             const uint8_t tv = type[m];
             const double xv = xi[m];
-            const double cv = xc[((int64_t)(k >> 1) * cny + (j >> 1)) * cnx + (i >> 1)];
+            const double cv = (double)xc[((int64_t)(k >> 1) * cny + (j >> 1)) * cnx + (i >> 1)];
             return (xv + ac * cv) * (double)(tv == 0);
         }
-        return xi[m];
+        return (double)xi[m];
     }
 };
 
@@ -336,14 +342,14 @@ __device__ inline double col_weight(const Grid& g, int i, int j) {
 
 // One damped Jacobi sweep on the finest level; with LAST the partials of
 // r.z (b . xo) are written, one per block.
-template <int MODE, bool LAST>
-__global__ __launch_bounds__(kBlock) void k_mg_fine_sweep(MgArgs a, MgLevel L, const double* __restrict__ xi,
-                                                           double* __restrict__ xo, const double* __restrict__ xc,
-                                                           MgLevel C, double alpha_c, int kc) {
+template <int MODE, bool LAST, typename TB>
+__global__ __launch_bounds__(kBlock) void k_mg_fine_sweep(MgArgs a, const TB* __restrict__ b0, const mgv* __restrict__ xi,
+                                                           mgv* __restrict__ xo, const mgv* __restrict__ xc, MgLevel C,
+                                                           double alpha_c, int kc) {
     DevState* s = a.s;
     if (s->done) return;
     const Grid& g = a.g;
-    FineIn<MODE> in{a.type, xi, L.b, xc, C.nx, C.ny, alpha_c};
+    FineIn<MODE, TB> in{a.type, xi, b0, xc, C.nx, C.ny, alpha_c};
     ZMarch t = zmarch(g.nx, g.ny, g.nz, kc);
     double rz = 0.0;
     if (t.col) {
@@ -375,7 +381,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_fine_sweep(MgArgs a, MgLevel L, c
             if (!up) vp = 0.0;
             const double xw = in(n + ow, iw, j, k, cwW), xe = in(n + oe, ie, j, k, cwE);
             const double xs = in(n + os, i, js, k, cwS), xn = in(n + on, i, jn, k, cwN);
-            const double bn = L.b[n];
+            const double bn = (double)b0[n];
             const bool fr = a.type[n] == 0;
             // a free node is never on a z face: fx = hy, fy = hx (hz = 1)
             double acc = 0.0;
@@ -385,8 +391,8 @@ __global__ __launch_bounds__(kBlock) void k_mg_fine_sweep(MgArgs a, MgLevel L, c
             acc += wn * (vc - xn);
             acc += fz * (vc - vm);
             acc += fz * (vc - vp);
-            const double out = (vc + cw * (bn - acc)) * (double)fr;  // values are finite
-            if (LAST) rz += bn * out;
+            const mgv out = (mgv)((vc + cw * (bn - acc)) * (double)fr);  // values are finite
+            if (LAST) rz += bn * (double)out;
             xo[n] = out;
             vm = vc;
             vc = vp;
@@ -403,7 +409,8 @@ __global__ __launch_bounds__(kBlock) void k_mg_fine_sweep(MgArgs a, MgLevel L, c
 // a coarse plane are in one block). The residuals of the two planes are added
 // in the thread, the x pair by a lane exchange and the y pair through LDS,
 // always as (even + odd).
-__global__ __launch_bounds__(kBlock) void k_mg_fine_restrict(MgArgs a, MgLevel L, const double* __restrict__ x,
+template <typename TB>
+__global__ __launch_bounds__(kBlock) void k_mg_fine_restrict(MgArgs a, const TB* __restrict__ b0, const mgv* __restrict__ x,
                                                               MgLevel C, int kc) {
     if (a.s->done) return;
     __shared__ double sh[4][64];
@@ -420,18 +427,18 @@ __global__ __launch_bounds__(kBlock) void k_mg_fine_restrict(MgArgs a, MgLevel L
     const int64_t ow = iw - i, oe = ie - i, os = (int64_t)(js - j) * g.nx, on = (int64_t)(jn - j) * g.nx;
     const double ww = i > 0 ? hy : 0.0, we = i < g.nx - 1 ? hy : 0.0;
     const double ws = j > 0 ? hx : 0.0, wn = j < g.ny - 1 ? hx : 0.0;
-    double vm = (col && t.k0 > 0) ? x[n - pl] : 0.0;
-    double vc = col ? x[n] : 0.0;
+    double vm = (col && t.k0 > 0) ? (double)x[n - pl] : 0.0;
+    double vc = col ? (double)x[n] : 0.0;
     double pair = 0.0;
     for (int k = t.k0; k < t.k1; ++k, n += pl) {
         double res = 0.0;
         double vp = 0.0;
         if (col) {
             const bool up = k + 1 < g.nz;
-            vp = x[up ? n + pl : n];
+            vp = (double)x[up ? n + pl : n];
             if (!up) vp = 0.0;
             const double xw = x[n + ow], xe = x[n + oe], xs = x[n + os], xn = x[n + on];
-            const double bn = L.b[n];
+            const double bn = (double)b0[n];
             const bool fr = a.type[n] == 0;
             double acc = 0.0;
             acc += ww * (vc - xw);
@@ -450,7 +457,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_fine_restrict(MgArgs a, MgLevel L
             __syncthreads();
             if (!(tx & 1) && !(ty & 1) && col) {
                 int64_t I = ((int64_t)(k >> 1) * C.ny + (j >> 1)) * C.nx + (i >> 1);
-                C.b[I] = sh[ty][tx] + sh[ty + 1][tx];
+                C.b[I] = (mgv)(sh[ty][tx] + sh[ty + 1][tx]);
             }
             __syncthreads();
             pair = 0.0;
@@ -546,8 +553,8 @@ int mg_setup(pic_ctx* c) {
         delete h;
         return -3;
     }
-    h->z[0] = (double*)take(nn * 8);
-    h->z[1] = (double*)take(nn * 8);
+    h->z[0] = (mgv*)take(nn * sizeof(mgv));
+    h->z[1] = (mgv*)take(nn * sizeof(mgv));
     h->part = (double*)take(64 * kMgBlocks * 8);
     for (int l = 0; l < h->nlev; ++l) {
         MgLevel& L = h->lv[l];
@@ -559,16 +566,16 @@ int mg_setup(pic_ctx* c) {
             L.diag = L.cx = L.cy = L.cz = nullptr;
             L.x0 = h->z[0];
             L.x1 = h->z[1];
-            L.b = c->cg_r;
+            L.b = nullptr;  // the finest right-hand side is passed to each V-cycle
             continue;
         }
-        L.diag = (double*)take(L.n * 8);
-        L.cx = (double*)take(L.n * 8);
-        L.cy = (double*)take(L.n * 8);
-        L.cz = (double*)take(L.n * 8);
-        L.x0 = (double*)take(L.n * 8);
-        L.x1 = (double*)take(L.n * 8);
-        L.b = (double*)take(L.n * 8);
+        L.diag = (mgv*)take(L.n * sizeof(mgv));
+        L.cx = (mgv*)take(L.n * sizeof(mgv));
+        L.cy = (mgv*)take(L.n * sizeof(mgv));
+        L.cz = (mgv*)take(L.n * sizeof(mgv));
+        L.x0 = (mgv*)take(L.n * sizeof(mgv));
+        L.x1 = (mgv*)take(L.n * sizeof(mgv));
+        L.b = (mgv*)take(L.n * sizeof(mgv));
     }
     MgLevel& Lc = h->lv[h->nlev - 1];
     h->cinv = (double*)take((size_t)Lc.n * Lc.n * 8);
@@ -595,15 +602,18 @@ int mg_setup(pic_ctx* c) {
     }
     // exact solve on the coarsest level
     int64_t m = Lc.n;
-    std::vector<double> dg(m), cx(m), cy(m), cz(m), inv;
-    if (hipMemcpyAsync(dg.data(), Lc.diag, m * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-        hipMemcpyAsync(cx.data(), Lc.cx, m * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-        hipMemcpyAsync(cy.data(), Lc.cy, m * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-        hipMemcpyAsync(cz.data(), Lc.cz, m * 8, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+    std::vector<mgv> dgf(m), cxf(m), cyf(m), czf(m);
+    std::vector<double> inv;
+    if (hipMemcpyAsync(dgf.data(), Lc.diag, m * sizeof(mgv), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipMemcpyAsync(cxf.data(), Lc.cx, m * sizeof(mgv), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipMemcpyAsync(cyf.data(), Lc.cy, m * sizeof(mgv), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+        hipMemcpyAsync(czf.data(), Lc.cz, m * sizeof(mgv), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
         delete h;
         return -2;
     }
+    std::vector<double> dg(dgf.begin(), dgf.end()), cx(cxf.begin(), cxf.end()), cy(cyf.begin(), cyf.end()),
+        cz(czf.begin(), czf.end());
     if (coarsest_inverse(Lc, dg, cx, cy, cz, inv) != 0) {
         delete h;
         return -3;
@@ -617,12 +627,14 @@ int mg_setup(pic_ctx* c) {
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-// z = V-cycle(r) on the finest level; returns the buffer holding z and, in
-// n_rz, the number of r.z partials written. The first kernel finishes r.r
-// and tests convergence, the last writes the partials of r.z. Every call
-// launches the same kernels with the same arguments.
-double* mg_vcycle(pic_ctx* c, double* part_rr, double* part_bb, double* part_rz, int cg_blocks, int* n_rz,
-                  bool timed) {
+// z = V-cycle(b0) on the finest level (b0: the CG residual, FP64 or FP32);
+// returns the buffer holding z and, in n_rz, the number of r.z partials
+// written. The first kernel finishes r.r and tests convergence, the last
+// writes the partials of r.z. Every call launches the same kernels with the
+// same arguments.
+template <typename TB>
+float* mg_vcycle(pic_ctx* c, const TB* b0, double* part_rr, double* part_bb, double* part_rz, int cg_blocks, int* n_rz,
+                 bool timed) {
     MgHier* h = (MgHier*)c->mg_host;
     MgArgs a;
     a.g = c->g;
@@ -632,9 +644,9 @@ double* mg_vcycle(pic_ctx* c, double* part_rr, double* part_bb, double* part_rz,
     a.part_bb = part_bb;
     a.part_rz = part_rz;
     const int nl = h->nlev;
-    const double* nul = nullptr;
-    double* pre_out[kMgMaxLevels];  // pre-smoothed iterate per level
-    double* res[kMgMaxLevels];      // final iterate per level
+    const mgv* nul = nullptr;
+    mgv* pre_out[kMgMaxLevels];  // pre-smoothed iterate per level
+    mgv* res[kMgMaxLevels];      // final iterate per level
     hipLaunchKernelGGL(k_mg_test, dim3(1), dim3(kBlock), 0, c->stream, a, cg_blocks);
     // descending: pre-smoothing (first sweep from zero + one sweep) and restriction
     for (int l = 0; l < nl - 1; ++l) {
@@ -642,20 +654,19 @@ double* mg_vcycle(pic_ctx* c, double* part_rr, double* part_bb, double* part_rz,
         MgLevel& C = h->lv[l + 1];
         if (l == 0) {
             int t1 = timed ? tic(c, PIC_T_MG_FIRST) : -1;
-            hipLaunchKernelGGL((k_mg_fine_sweep<kFineFirst, false>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream, a,
-                               L, nul, L.x0, nul, C, 0.0, h->zm_kc);
+            hipLaunchKernelGGL((k_mg_fine_sweep<kFineFirst, false, TB>), dim3(h->zm_blocks), dim3(kBlock), 0,
+                               c->stream, a, b0, nul, L.x0, nul, C, 0.0, h->zm_kc);
             toc(c, t1);
             int t2 = timed ? tic(c, PIC_T_MG_RESTRICT) : -1;
-            hipLaunchKernelGGL(k_mg_fine_restrict, dim3(h->zr_blocks), dim3(kBlock), 0, c->stream, a, L,
-                               (const double*)L.x0, C, h->zr_kc);
+            hipLaunchKernelGGL(k_mg_fine_restrict<TB>, dim3(h->zr_blocks), dim3(kBlock), 0, c->stream, a, b0,
+                               (const mgv*)L.x0, C, h->zr_kc);
             toc(c, t2);
             pre_out[0] = L.x0;
         } else {
             hipLaunchKernelGGL(k_mg_first, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L);
-            hipLaunchKernelGGL(k_mg_jacobi, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L, (const double*)L.x0,
-                               L.x1, nul, C, 0.0);
-            hipLaunchKernelGGL(k_mg_restrict, dim3(mg_grid(C.n)), dim3(kBlock), 0, c->stream, a, L, (const double*)L.x1,
-                               C);
+            hipLaunchKernelGGL(k_mg_jacobi, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L, (const mgv*)L.x0, L.x1,
+                               nul, C, 0.0);
+            hipLaunchKernelGGL(k_mg_restrict, dim3(mg_grid(C.n)), dim3(kBlock), 0, c->stream, a, L, (const mgv*)L.x1, C);
             pre_out[l] = L.x1;
         }
     }
@@ -666,22 +677,22 @@ double* mg_vcycle(pic_ctx* c, double* part_rr, double* part_bb, double* part_rz,
     for (int l = nl - 2; l >= 0; --l) {
         MgLevel& L = h->lv[l];
         MgLevel& C = h->lv[l + 1];
-        double* xi = pre_out[l];
-        double* xo = xi == L.x0 ? L.x1 : L.x0;
+        mgv* xi = pre_out[l];
+        mgv* xo = xi == L.x0 ? L.x1 : L.x0;
         if (l == 0) {
             int t1 = timed ? tic(c, PIC_T_MG_CORR) : -1;
-            hipLaunchKernelGGL((k_mg_fine_sweep<kFineCorr, false>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream, a,
-                               L, (const double*)xi, xo, (const double*)res[1], C, h->alpha_c, h->zm_kc);
+            hipLaunchKernelGGL((k_mg_fine_sweep<kFineCorr, false, TB>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream,
+                               a, b0, (const mgv*)xi, xo, (const mgv*)res[1], C, h->alpha_c, h->zm_kc);
             toc(c, t1);
             int t2 = timed ? tic(c, PIC_T_MG_LAST) : -1;
-            hipLaunchKernelGGL((k_mg_fine_sweep<kFinePlain, true>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream, a,
-                               L, (const double*)xo, xi, nul, C, 0.0, h->zm_kc);
+            hipLaunchKernelGGL((k_mg_fine_sweep<kFinePlain, true, TB>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream,
+                               a, b0, (const mgv*)xo, xi, nul, C, 0.0, h->zm_kc);
             toc(c, t2);
         } else {
-            hipLaunchKernelGGL(k_mg_jacobi, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L, (const double*)xi, xo,
-                               (const double*)res[l + 1], C, h->alpha_c);
-            hipLaunchKernelGGL(k_mg_jacobi, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L, (const double*)xo, xi,
-                               nul, C, 0.0);
+            hipLaunchKernelGGL(k_mg_jacobi, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L, (const mgv*)xi, xo,
+                               (const mgv*)res[l + 1], C, h->alpha_c);
+            hipLaunchKernelGGL(k_mg_jacobi, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L, (const mgv*)xo, xi, nul,
+                               C, 0.0);
         }
         res[l] = xi;
     }
@@ -689,11 +700,13 @@ double* mg_vcycle(pic_ctx* c, double* part_rr, double* part_bb, double* part_rz,
     return res[0];
 }
 
+template float* mg_vcycle<double>(pic_ctx*, const double*, double*, double*, double*, int, int*, bool);
+template float* mg_vcycle<float>(pic_ctx*, const float*, double*, double*, double*, int, int*, bool);
+
 void mg_free(pic_ctx* c) {
     delete (MgHier*)c->mg_host;
     c->mg_host = nullptr;
 }
 
-int mixed_solve(pic_ctx*, double*, double, const int64_t*, int, double, int, pic_solve_info*) { return -3; }
 
 }  // namespace pic

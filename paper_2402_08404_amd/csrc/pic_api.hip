@@ -482,6 +482,8 @@ void pic_destroy(pic_ctx* c) {
     if (c->host_st) (void)hipHostFree(c->host_st);
     if (c->pcg_exec) (void)hipGraphExecDestroy(c->pcg_exec);
     if (c->pcg_graph) (void)hipGraphDestroy(c->pcg_graph);
+    if (c->mix_exec) (void)hipGraphExecDestroy(c->mix_exec);
+    if (c->mix_graph) (void)hipGraphDestroy(c->mix_graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     mg_free(c);
     delete c;

@@ -349,8 +349,9 @@ struct pic_ctx {
     // captured pair of preconditioned CG iterations (built at the first
     // unprofiled multigrid solve)
     hipStream_t cap_stream = nullptr;
-    hipGraph_t pcg_graph = nullptr;
-    hipGraphExec_t pcg_exec = nullptr;
+    hipGraph_t pcg_graph = nullptr, mix_graph = nullptr;
+    hipGraphExec_t pcg_exec = nullptr, mix_exec = nullptr;
+    int last_iters[3] = {0, 0, 0};   // iterations of the last solve per solver (first launch chunk)
     int learn_smooth = 0;            // binomial filter passes on its output
     // host state
     pic::DevState* host_st = nullptr;  // pinned mirror
@@ -384,8 +385,10 @@ int mgcg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess
 int mixed_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess, double rtol, int maxit,
                 pic_solve_info* info);
 size_t mg_bytes(const pic_config* cfg);
-double* mg_vcycle(pic_ctx* c, double* part_rr, double* part_bb, double* part_rz, int cg_blocks, int* n_rz,
-                  bool timed);
+// z = V-cycle(b0) (FP32 z); b0 is the CG residual of the finest level
+template <typename TB>
+float* mg_vcycle(pic_ctx* c, const TB* b0, double* part_rr, double* part_bb, double* part_rz, int cg_blocks, int* n_rz,
+                 bool timed);
 void mg_free(pic_ctx* c);
 hipError_t scan_u32(pic_ctx* c, const uint32_t* in, uint32_t* out, int64_t n_max, const uint32_t* nd,
                     uint32_t* total, bool zero_in, bool popcount);

@@ -334,3 +334,54 @@ def test_mgcg_solve_parity(precision):
     # the plain CG of the library from the same state agrees with both
     info2 = g.solve(solver=pic.PIC_SOLVER_CG, guess=pic.PIC_GUESS_ZERO, rtol=1e-13)
     assert np.abs(g.grid("phi") - o.phi).max() <= 1e-10 * np.abs(o.phi).max()
+
+
+def test_mixed_solve_parity():
+    """Mixed precision (FP64 residual refinement around FP32 multigrid-
+    preconditioned CG with FP64 dot products) reaches a 1e-10 relative
+    residual, and the potential of the oracle's FP64 solve."""
+    cfg = W.tiny()
+    load = W.initial_load(cfg, counts=(20000, 200, 0), seed=8)
+    g, o, _ = _pair(cfg, load, F32)
+    g.step(1, pic.STEP_DEPOSIT)
+    o.deposit()
+    info = g.solve(solver=pic.PIC_SOLVER_MIXED, guess=pic.PIC_GUESS_ZERO, rtol=1e-10)
+    o.solve(rtol=1e-13, guess="zero")
+    print("mixed", info, flush=True)
+    assert info["converged"] and info["relres"] <= 1e-10
+    err = np.abs(g.grid("phi") - o.phi).max() / np.abs(o.phi).max()
+    assert err <= 1e-8, err
+    # from the previous solution it returns at once
+    info2 = g.solve(solver=pic.PIC_SOLVER_MIXED, guess=pic.PIC_GUESS_PREVIOUS, rtol=1e-10)
+    assert info2["converged"] and info2["iterations"] == 0
+
+
+def test_precision_variant_error_report():
+    """The precision variant (FP32 particle state, fixed-point deposit,
+    mixed-precision solve to 1e-10) against the FP64 oracle over 20 whole
+    steps of the tiny configuration: the potential, the Shockley-Ramo current
+    and the ion count. Trajectories drift apart at FP32 rounding and the
+    first differing collision decision makes the two runs different
+    realizations, so the bounds are statistical; the measured errors are
+    printed."""
+    cfg = W.tiny()
+    load = W.initial_load(cfg)
+    g, o, _ = _pair(cfg, load, F32, solver=pic.PIC_SOLVER_MIXED, step_rtol=1e-10)
+    g.step(1, pic.STEP_DEPOSIT)
+    g.solve(solver=pic.PIC_SOLVER_MIXED, rtol=1e-10)
+    o.deposit()
+    o.solve(rtol=1e-12)
+    errs = []
+    for s in range(20):
+        g.step(1, pic.STEP_FULL)
+        o.step(rtol=1e-12)
+        mg, mo = g.moments(), o.moments()
+        phi_err = np.linalg.norm(g.grid("phi") - o.phi) / np.linalg.norm(o.phi)
+        cur_err = abs(mg["i_sr"] - mo["i_sr"]) / max(abs(mo["i_sr"]), 1e-30)
+        ion_err = abs(int(mg["n_alive"][1]) - int(mo["n"][1])) / max(int(mo["n"][1]), 1)
+        errs.append((phi_err, cur_err, ion_err))
+    errs = np.array(errs)
+    print("step errors (potential L2, current, ion count):", errs[[0, 4, 9, 19]].tolist(), flush=True)
+    assert errs[:, 0].max() < 1e-3
+    assert errs[:, 2].max() < 0.05
+    assert errs[:5, 1].max() < 1e-3
