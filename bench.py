@@ -113,6 +113,13 @@ def main():
     ap.add_argument("--skip-zero-solve", action="store_true")
     ap.add_argument("--prof-steps", type=int, default=5,
                     help="steps of the profiled pass after the timed region (per-kernel HIP-event timings)")
+    ap.add_argument("--batch", action="store_true",
+                    help="the batched field sweep (16 instances at 6.0 ... 13.5 GV/m, 1 M - 40 M particles) instead")
+    ap.add_argument("--batch-scale", type=float, default=1.0, help="scale factor of the sweep's particle counts")
+    ap.add_argument("--autotune", action="store_true", help="with --batch: autotune first and store the choices")
+    ap.add_argument("--batch-compare", action="store_true",
+                    help="with --batch: also time the same steps with the instances stepped one after another")
+    ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2402_08404_amd", "tuning.json"))
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (the reference kernel that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
@@ -137,6 +144,9 @@ def main():
 
     def log(*a):
         print(*a, file=sys.stderr, flush=True)
+
+    if args.batch:
+        return batch_main(args, log)
 
     cfg, counts, kT, region, np = workload(args.workload)
     solver = {"cg": pic.PIC_SOLVER_CG, "mgcg": pic.PIC_SOLVER_MGCG, "mixed": pic.PIC_SOLVER_MIXED}[args.solver]
@@ -250,6 +260,51 @@ def main():
     else:
         out["cpu_baseline"] = None
     sim.close()
+    print(json.dumps(out), flush=True)
+
+
+def batch_main(args, log):
+    """The batched sweep: concurrent instances, whole-job particle-steps/s."""
+    import torch
+    from paper_2402_08404_amd import batch, pic
+    items = batch.sweep_configs(16, scale=args.batch_scale)
+    tuning = batch.load_tuning(args.tuning)
+    if args.autotune:
+        tuning = batch.autotune(items, log=log)
+        batch.save_tuning(tuning, args.tuning)
+    t0 = time.perf_counter()
+    b = batch.Batch(items, tuning=tuning)
+    log(f"[bench] batch of {len(items)} instances ready ({time.perf_counter() - t0:.1f} s), "
+        f"{sum(sum(c) for _, c in items)} particles")
+    b.step(args.warmup)
+    n0 = b.alive()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(args.steps)
+    wall = time.perf_counter() - t0
+    n1 = b.alive()
+    value = 0.5 * (n0 + n1) * args.steps / wall
+    serial = None
+    if args.batch_compare:
+        # the same number of steps with one instance at a time (no overlap)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for s in b.sims:
+            s.step(args.steps, pic.STEP_FULL)
+            torch.cuda.synchronize()
+        serial = 1e3 * (time.perf_counter() - t1) / args.steps
+    out = {
+        "metric": "particle-steps/s (batched field sweep, push+deposit+MCC+solve)",
+        "value": float(value), "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "field_sweep_16", "fields_GVm": [round(c.apex_field / 1e9, 2) for c, _ in items],
+                   "grids": [[c.nx, c.ny, c.nz] for c, _ in items], "particles": [sum(n) for _, n in items],
+                   "tuning": tuning},
+        "alive": [n0, n1],
+        "serial_ms_per_step": serial,
+    }
+    b.close()
     print(json.dumps(out), flush=True)
 
 

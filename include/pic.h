@@ -110,6 +110,7 @@ typedef struct pic_config {
     int32_t step_maxit;    /* iteration limit of the solve inside pic_step */
     int32_t sort_every;    /* reorder particles by cell every this many collide phases (0: never) */
     int64_t id_capacity;   /* largest particle id + 1 the run may reach (0: 8 x total capacity) */
+    int32_t stencil_blocks; /* about this many blocks per z-marching solver kernel (0: 1024; 64..2048) */
 } pic_config;
 
 typedef struct pic_buffers {

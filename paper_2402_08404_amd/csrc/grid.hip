@@ -582,7 +582,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_b(PcgArgs<TP> a, const double* p
 }
 
 // Partials of the mixed-precision refinement live after the CG ones.
-constexpr int kPartPq = 0, kPartRr = 2048, kPartBb = 4096, kPartRz = 6144;
+constexpr int kPartPq = 0, kPartRr = 4096, kPartBb = 8192, kPartRz = 12288;
 
 // Run the preconditioned iterations on x, r (type TP; r also the V-cycle's
 // right-hand side) after k_cg_setup and the partials of r.r and b.b are in
@@ -604,8 +604,8 @@ static int pcg_iterate(pic_ctx* c, TP* x, TP* r, TP* p0, TP* p1, TP* q, int maxi
     double* part_rz = c->partials + kPartRz;
     a.chunk = ((g.nn + kCgBlocks - 1) / kCgBlocks + kBlock - 1) / kBlock * kBlock;
     int kc = 1;
-    unsigned zb = zmarch_grid(g.nx, g.ny, g.nz, kCgBlocks, 1, &kc);
-    if (zb > 2048) return -3;
+    unsigned zb = zmarch_grid(g.nx, g.ny, g.nz, stencil_target(c), 1, &kc);
+    if (zb > 4096) return -3;
     // one iteration: V-cycle, p update and A p, x and r update
     auto iteration = [&](TP* p_old, TP* p_new, bool timed) {
         int tm = timed ? tic(c, PIC_T_MG) : -1;

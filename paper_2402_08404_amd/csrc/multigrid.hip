@@ -586,9 +586,9 @@ int mg_setup(pic_ctx* c) {
     h->pre = 2;
     h->post = 2;
     h->alpha_c = 2.0;
-    h->zm_blocks = zmarch_grid(c->g.nx, c->g.ny, c->g.nz, kMgBlocks, 1, &h->zm_kc);
-    h->zr_blocks = zmarch_grid(c->g.nx, c->g.ny, c->g.nz, kMgBlocks, 2, &h->zr_kc);
-    if (h->zm_blocks > 2048) {
+    h->zm_blocks = zmarch_grid(c->g.nx, c->g.ny, c->g.nz, stencil_target(c), 1, &h->zm_kc);
+    h->zr_blocks = zmarch_grid(c->g.nx, c->g.ny, c->g.nz, stencil_target(c), 2, &h->zr_kc);
+    if (h->zm_blocks > 4096) {
         delete h;
         return -3;
     }

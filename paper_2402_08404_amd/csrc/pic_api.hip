@@ -51,6 +51,8 @@ const char* check_config(const pic_config* cfg) {
     if (!(cfg->phi_w > 0) || !(cfg->xi > 0) || !(cfg->m_ion > 0)) return "phi_w, xi, m_ion must be positive";
     if (!(cfg->laplace_rtol > 0) || !(cfg->step_rtol > 0) || cfg->step_maxit < 1) return "bad solver tolerances";
     if (cfg->sort_every < 0) return "sort_every must be >= 0";
+    if (cfg->stencil_blocks != 0 && (cfg->stencil_blocks < 64 || cfg->stencil_blocks > 2048))
+        return "stencil_blocks must be 0 or in 64..2048";
     if (cfg->id_capacity < 0 || cfg->id_capacity > ((int64_t)1 << 32)) return "id_capacity out of range";
     return nullptr;
 }
@@ -89,7 +91,7 @@ size_t pic::scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[
     size_t tsz = cfg->precision == PIC_F32 ? 4 : 8;
     int64_t scan_n = std::max(std::max(nc + 1, 256 * ((capsum + 4095) / 4096 + 1)), std::max(capsum, words));
     int64_t scan_blocks = (scan_n + 4095) / 4096 + 1;
-    int64_t parts = std::max<int64_t>(4 * 2048, 8 * 512) + 64;  // CG/MG partials (4 x 2048), moments (8 x 512)
+    int64_t parts = std::max<int64_t>(4 * 4096, 8 * 512) + 64;  // CG/MG partials (4 x 4096), moments (8 x 512)
     pic_ctx dummy;
     pic_ctx* t = c ? c : &dummy;
     t->st = (DevState*)take(sizeof(DevState));

@@ -373,6 +373,8 @@ struct pic_ctx {
 };
 
 namespace pic {
+// target block count of the z-marching solver kernels
+inline int stencil_target(const pic_ctx* c) { return c->cfg.stencil_blocks ? c->cfg.stencil_blocks : 1024; }
 size_t scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[3], char* base);
 hipError_t launch_node_types(pic_ctx* c);
 hipError_t launch_field(pic_ctx* c, const double* phi, void* field);
