@@ -70,6 +70,69 @@ SOLVER_BYTES_PER_NODE = {
 }
 
 
+# Device symbol of each timed kernel (for the rocprofv3 traffic summary).
+KERNEL_SYMBOLS = {
+    "push_electrons": "k_push<float, 0, true>",
+    "cg_a": "k_pcg_a<double>",
+    "cg_b": "k_pcg_b<double>",
+    "mg_first": "k_mg_fine_sweep<1, false, double>",
+    "mg_restrict": "k_mg_fine_restrict<double>",
+    "mg_corr": "k_mg_fine_sweep<2, false, double>",
+    "mg_last": "k_mg_fine_sweep<0, true, double>",
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gpu_scale.json")
+
+
+def pmc_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib, out_path):
+    """HBM bytes per dispatch of every kernel from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE; KiB per dispatch, median over dispatches of the
+    largest grid of each kernel), each scaled by what the same counter reads
+    for a plain device copy of copy_mib MiB."""
+    import csv
+    import statistics
+
+    def per_kernel(path):
+        d = {}
+        for r in csv.DictReader(open(path)):
+            name = r["Kernel_Name"].split("(")[0].replace("void ", "").strip()
+            d.setdefault((name, int(r["Grid_Size"])), []).append(float(r["Counter_Value"]))
+        best = {}
+        for (name, grid), v in d.items():
+            if name not in best or grid > best[name][0]:
+                best[name] = (grid, statistics.median(v), len(v))
+        return best
+
+    def copy_kib(path):
+        v = [float(r["Counter_Value"]) for r in csv.DictReader(open(path)) if "copyBuffer" in r["Kernel_Name"]
+             or "copy" in r["Kernel_Name"].lower()]
+        return statistics.median(v)
+
+    f_fetch = copy_mib * 1024.0 / copy_kib(copy_fetch_csv)
+    f_write = copy_mib * 1024.0 / copy_kib(copy_write_csv)
+    fe, wr = per_kernel(fetch_csv), per_kernel(write_csv)
+    out = {"fetch_scale": f_fetch, "write_scale": f_write, "copy_mib": copy_mib, "kernels": {}}
+    for name in sorted(set(fe) & set(wr)):
+        out["kernels"][name] = {"grid": fe[name][0], "fetch_kib": fe[name][1], "write_kib": wr[name][1],
+                                "dispatches": fe[name][2],
+                                "bytes": 1024.0 * (fe[name][1] * f_fetch + wr[name][1] * f_write)}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1, sort_keys=True)
+    return out
+
+
+def measured_traffic(kernel: str):
+    """Scaled HBM bytes per launch of a kernel from the committed summary, or None."""
+    sym = KERNEL_SYMBOLS.get(kernel)
+    if not sym or not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    for name, v in t["kernels"].items():
+        if name.endswith(sym):
+            return v["bytes"]
+    return None
+
+
 def cpu_baseline(cfg_name, sample, steps, np):
     """The CPU oracle (single thread, FP64) on a bounded sample of the same
     workload: `sample` particles with the same species mix and distributions
@@ -120,6 +183,9 @@ def main():
     ap.add_argument("--batch-compare", action="store_true",
                     help="with --batch: also time the same steps with the instances stepped one after another")
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2402_08404_amd", "tuning.json"))
+    ap.add_argument("--pmc-summary", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV",
+                                                        "COPY_MIB"),
+                    help="write the HBM traffic summary of rocprofv3 --pmc runs to profiles/ and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (the reference kernel that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
@@ -129,6 +195,11 @@ def main():
               "described in DESIGN.md but not built", file=sys.stderr)
         sys.exit(2)
 
+    if args.pmc_summary:
+        a = args.pmc_summary
+        out = pmc_summary(a[0], a[1], a[2], a[3], float(a[4]), TRAFFIC_FILE)
+        print(json.dumps({k: round(v["bytes"] / 1e6, 1) for k, v in out["kernels"].items()}, indent=1))
+        return
     import torch
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 4
@@ -154,8 +225,12 @@ def main():
     caps = (counts[0] + counts[2] + max(counts[0] // 8, 4096), counts[1] + counts[2] + max(counts[1] // 8, 4096),
             counts[2] + 1024)
     t_setup = time.perf_counter()
+    # launch settings chosen by the autotuner for this grid shape, if it has run
+    from paper_2402_08404_amd import batch as B
+    tune = B.load_tuning(args.tuning).get(B.shape_key(cfg), {})
+    stencil_blocks = int(tune.get("stencil_blocks", 0))
     sim = pic.Simulation(cfg, caps=caps, precision=pic.PIC_F32 if fp32 else pic.PIC_F64, solver=solver,
-                         step_rtol=1e-8, step_maxit=20000, sort_every=args.sort_every)
+                         step_rtol=1e-8, step_maxit=20000, sort_every=args.sort_every, stencil_blocks=stencil_blocks)
     log(f"[bench] init done ({time.perf_counter() - t_setup:.1f} s), generating {sum(counts)} particles")
     load = W.initial_load(cfg, counts=counts, kT_eV=kT, region=region,
                           dtype=np.float32 if fp32 else np.float64)
@@ -222,8 +297,9 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"]
               if kernels[k]["launches"] else -1.0)
     k = kernels[dom]
+    traffic = measured_traffic(dom)
     roof = {"kernel": dom, "bound": "hbm", "achieved": round(k["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(k["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(k["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic,
             "bytes_per_launch": k["bytes"], "avg_launch_ms": k["avg_ms"]}
 
     out = {
@@ -241,7 +317,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": [cfg.nx, cfg.ny, cfg.nz], "h_m": cfg.h,
                    "particles": list(counts), "particle_state": "fp32" if fp32 else "fp64",
-                   "poisson": f"{args.solver} fp64 rtol 1e-8, previous-step guess", "sort_every": args.sort_every},
+                   "poisson": f"{args.solver} fp64 rtol 1e-8, previous-step guess", "sort_every": args.sort_every,
+                   "stencil_blocks": stencil_blocks or 1024},
         "roofline": roof,
         "profiled_pass_ms_per_step": {k2: tm[k2][0] / psteps for k2 in
                                       ("inject", "particles", "push", "collide", "mcc", "solve", "step")},

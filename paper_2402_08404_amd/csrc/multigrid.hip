@@ -206,13 +206,15 @@ __global__ void k_mg_test(MgArgs a, int cg_blocks) {
 }
 
 // First sweep from x = 0 on a coarse level: x = omega D^-1 b.
+// (The small coarse-level kernels issue their loads before testing whether
+// the solve is done, so the two latencies overlap.)
 __global__ __launch_bounds__(kBlock) void k_mg_first(MgArgs a, MgLevel L) {
     DevState* s = a.s;
-    if (s->done) return;
     int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= L.n) return;
-    double d = L.diag[n];
-    L.x0[n] = (mgv)(d == 0.0 ? 0.0 : kOmega * (double)L.b[n] / d);
+    const double d = L.diag[n], bn = L.b[n];
+    if (s->done) return;
+    L.x0[n] = (mgv)(d == 0.0 ? 0.0 : kOmega * bn / d);
 }
 
 // One damped Jacobi sweep on a coarse level, xo = xi + omega D^-1 (b - A xi),
@@ -222,15 +224,9 @@ __global__ __launch_bounds__(kBlock) void k_mg_jacobi(MgArgs a, MgLevel L, const
                                                        mgv* __restrict__ xo, const mgv* __restrict__ xc, MgLevel C,
                                                        double alpha_c) {
     DevState* s = a.s;
-    if (s->done) return;
     int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= L.n) return;
     int i = (int)(n % L.nx), j = (int)((n / L.nx) % L.ny), k = (int)(n / ((int64_t)L.nx * L.ny));
-    double d = L.diag[n];
-    if (d == 0.0) {
-        xo[n] = (mgv)0;
-        return;
-    }
     auto val = [&](int64_t m, int ii, int jj, int kk) -> double {
         double v = xi[m];
         if (xc) v += alpha_c * (double)xc[((int64_t)(kk / 2) * C.ny + jj / 2) * C.nx + ii / 2];
@@ -243,10 +239,12 @@ __global__ __launch_bounds__(kBlock) void k_mg_jacobi(MgArgs a, MgLevel L, const
     const int kb = k > 0 ? k - 1 : k, kt = k < L.nz - 1 ? k + 1 : k;
     const int64_t ow = iw - i, oe = ie - i, os = (int64_t)(js - j) * L.nx, on = (int64_t)(jn - j) * L.nx;
     const int64_t ob = (int64_t)(kb - k) * pl, ot = (int64_t)(kt - k) * pl;
+    const double d = L.diag[n], bn = L.b[n];
     const double cw = L.cx[n + ow], ce = L.cx[n], cs = L.cy[n + os], cn = L.cy[n], cb = L.cz[n + ob], ct = L.cz[n];
     const double xn = val(n, i, j, k);
     const double xw = val(n + ow, iw, j, k), xe = val(n + oe, ie, j, k), xs = val(n + os, i, js, k),
                  xnn = val(n + on, i, jn, k), xb = val(n + ob, i, j, kb), xt = val(n + ot, i, j, kt);
+    if (s->done) return;
     double sacc = d * xn;
     sacc += (i > 0 ? cw : 0.0) * xw;
     sacc += (i < L.nx - 1 ? ce : 0.0) * xe;
@@ -254,32 +252,36 @@ __global__ __launch_bounds__(kBlock) void k_mg_jacobi(MgArgs a, MgLevel L, const
     sacc += (j < L.ny - 1 ? cn : 0.0) * xnn;
     sacc += (k > 0 ? cb : 0.0) * xb;
     sacc += (k < L.nz - 1 ? ct : 0.0) * xt;
-    xo[n] = (mgv)(xn + kOmega * ((double)L.b[n] - sacc) / d);
+    // a node without an unknown (diag 0) stays zero
+    xo[n] = (mgv)(d == 0.0 ? 0.0 : xn + kOmega * (bn - sacc) / (d == 0.0 ? 1.0 : d));
 }
 
-// b_c = P^T (b - A x) between two coarse levels: each coarse node sums the
-// residuals of its children.
+// b_c = P^T (b - A x) between two coarse levels: eight consecutive threads
+// per coarse node, one per child, summed in a fixed order by lane exchanges
+// ((c0 + c1) + (c2 + c3)) + ((c4 + c5) + (c6 + c7)).
 __global__ __launch_bounds__(kBlock) void k_mg_restrict(MgArgs a, MgLevel F, const mgv* __restrict__ x, MgLevel C) {
-    if (a.s->done) return;
-    int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (I >= C.n) return;
-    int Ix = (int)(I % C.nx), Iy = (int)((I / C.nx) % C.ny), Iz = (int)(I / ((int64_t)C.nx * C.ny));
-    double sum = 0.0;
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        int i = 2 * Ix + (t & 1), j = 2 * Iy + ((t >> 1) & 1), k = 2 * Iz + ((t >> 2) & 1);
-        const bool in = i < F.nx && j < F.ny && k < F.nz;
-        // a child outside the grid is evaluated at the first child, weight zero
-        if (!in) {
-            i = 2 * Ix;
-            j = 2 * Iy;
-            k = 2 * Iz;
-        }
-        int64_t n = ((int64_t)k * F.ny + j) * F.nx + i;
-        const double r = (double)F.b[n] - apply_coarse(F, x, n, i, j, k, x[n]);
-        sum += (in && F.diag[n] != (mgv)0) ? r : 0.0;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t I = gid >> 3;
+    const int t = (int)(gid & 7);
+    const bool valid = I < C.n;
+    const int64_t Ic = valid ? I : C.n - 1;
+    const int Ix = (int)(Ic % C.nx), Iy = (int)((Ic / C.nx) % C.ny), Iz = (int)(Ic / ((int64_t)C.nx * C.ny));
+    int i = 2 * Ix + (t & 1), j = 2 * Iy + ((t >> 1) & 1), k = 2 * Iz + ((t >> 2) & 1);
+    const bool in = i < F.nx && j < F.ny && k < F.nz;
+    // a child outside the grid is evaluated at the first child, weight zero
+    if (!in) {
+        i = 2 * Ix;
+        j = 2 * Iy;
+        k = 2 * Iz;
     }
-    C.b[I] = (mgv)sum;
+    const int64_t n = ((int64_t)k * F.ny + j) * F.nx + i;
+    const double r = (double)F.b[n] - apply_coarse(F, x, n, i, j, k, x[n]);
+    double v = (in && F.diag[n] != (mgv)0) ? r : 0.0;
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    if (a.s->done) return;
+    if (t == 0 && valid) C.b[I] = (mgv)v;
 }
 
 // Coarsest level: x = A^-1 b with the stored inverse, one wavefront per row.
@@ -666,7 +668,8 @@ float* mg_vcycle(pic_ctx* c, const TB* b0, double* part_rr, double* part_bb, dou
             hipLaunchKernelGGL(k_mg_first, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L);
             hipLaunchKernelGGL(k_mg_jacobi, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L, (const mgv*)L.x0, L.x1,
                                nul, C, 0.0);
-            hipLaunchKernelGGL(k_mg_restrict, dim3(mg_grid(C.n)), dim3(kBlock), 0, c->stream, a, L, (const mgv*)L.x1, C);
+            hipLaunchKernelGGL(k_mg_restrict, dim3(mg_grid(8 * C.n)), dim3(kBlock), 0, c->stream, a, L, (const mgv*)L.x1,
+                               C);
             pre_out[l] = L.x1;
         }
     }
