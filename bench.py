@@ -176,6 +176,8 @@ def main():
     ap.add_argument("--skip-zero-solve", action="store_true")
     ap.add_argument("--prof-steps", type=int, default=5,
                     help="steps of the profiled pass after the timed region (per-kernel HIP-event timings)")
+    ap.add_argument("--unet", action="store_true",
+                    help="time the warm-start network (forward, and forward + backward + Adam) at 1 x 512 x 128 x 128")
     ap.add_argument("--batch", action="store_true",
                     help="the batched field sweep (16 instances at 6.0 ... 13.5 GV/m, 1 M - 40 M particles) instead")
     ap.add_argument("--batch-scale", type=float, default=1.0, help="scale factor of the sweep's particle counts")
@@ -218,6 +220,8 @@ def main():
 
     if args.batch:
         return batch_main(args, log)
+    if args.unet:
+        return unet_main(args, log)
 
     cfg, counts, kT, region, np = workload(args.workload)
     solver = {"cg": pic.PIC_SOLVER_CG, "mgcg": pic.PIC_SOLVER_MGCG, "mixed": pic.PIC_SOLVER_MIXED}[args.solver]
@@ -337,6 +341,61 @@ def main():
     else:
         out["cpu_baseline"] = None
     sim.close()
+    print(json.dumps(out), flush=True)
+
+
+def unet_flops(d: int, h: int, w: int, base: int = 16) -> float:
+    """Multiply-add FLOPs (2 per MAC) of one forward pass over d x h x w: each
+    layer costs taps x cin x cout MACs per output voxel of its GEMM rows (the
+    8-channel input counts its 8 channels, as the kernels compute them)."""
+    c = [base, 2 * base, 4 * base, 8 * base]
+    vox = [d * h * w / 8 ** l for l in range(4)]
+    layers = [(27, 8, c[0], 0), (27, c[0], c[0], 0)]
+    for lv in (1, 2, 3):
+        layers += [(8, c[lv - 1], c[lv], lv), (27, c[lv], c[lv], lv), (27, c[lv], c[lv], lv)]
+    for lv in (2, 1, 0):
+        layers += [(8, c[lv + 1], c[lv], lv), (27, 2 * c[lv], c[lv], lv), (27, c[lv], c[lv], lv)]
+    macs = sum(t * ci * co * vox[lv] for t, ci, co, lv in layers)
+    # the transposed convolutions: 8 taps over coarse voxels = 1 tap over fine voxels
+    macs -= sum(7 * c[lv + 1] * c[lv] * vox[lv] for lv in (2, 1, 0))
+    return 2.0 * macs + 2.0 * base * vox[0]
+
+
+def unet_main(args, log):
+    """Throughput of the warm-start network's bf16 MFMA kernels."""
+    import torch
+    from paper_2402_08404_amd import pic
+    D, H, Wd = 512, 128, 128
+    net = pic.UNet(1, D, H, Wd, seed=1)
+    x = torch.randn(1, D, H, Wd, device="cuda")
+    t = torch.randn(1, D, H, Wd, device="cuda")
+    for _ in range(args.warmup):
+        net.forward(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.forward(x)
+    torch.cuda.synchronize()
+    fwd = (time.perf_counter() - t0) / args.steps
+    for _ in range(args.warmup):
+        net.train_step(x, t, 1e-4, want_loss=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.train_step(x, t, 1e-4, want_loss=False)
+    torch.cuda.synchronize()
+    trn = (time.perf_counter() - t0) / args.steps
+    fl = unet_flops(D, H, Wd)
+    peak = 2500.0
+    out = {"metric": "warm-start network throughput (bf16 MFMA, fp32 accumulate)", "value": fl / fwd / 1e12,
+           "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * fwd,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+           "config": {"workload": "unet_1x512x128x128", "params": net.n_params},
+           "roofline": {"bound": "mfma", "achieved": fl / fwd / 1e12, "peak": peak, "unit": "TFLOP/s",
+                        "frac": fl / fwd / 1e12 / peak, "traffic": None},
+           "forward_ms": 1e3 * fwd, "train_step_ms": 1e3 * trn, "forward_tflop": fl / 1e12,
+           "train_tflops_est": 3 * fl / trn / 1e12}
+    net.close()
     print(json.dumps(out), flush=True)
 
 

@@ -705,3 +705,26 @@ def test_step_bookkeeping_and_charge():
         assert ni + m["absorbed"][1].sum() == 200 + created
         assert nn + m["absorbed"][2].sum() == 2000 - created
         assert o.next_id == loaded + m["injected"] + 2 * created
+
+
+def test_adk_rate_uses_the_printed_constants():
+    """The oracle's field-ionization rate is Eq. dfi with the constants the
+    paper prints (tests/golden/adk_eq_dfi.txt), for z = 1 and Cu's xi."""
+    import math
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "adk_eq_dfi.txt")
+    k = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            name, val = line.split()
+            k[name] = float(val)
+    cfg = W.tiny()
+    o = oracle.Oracle(cfg, laplace=False)
+    xi = cfg.xi
+    n = k["N"] * xi ** -0.5
+    for E in (6.0, 8.0, 10.0, 12.0, 14.0):
+        want = (k["C"] * 4 ** n * xi / (n * math.gamma(2 * n)) * (k["A"] * xi ** 1.5 / E) ** (2 * n - 1)
+                * math.exp(-k["B"] * xi ** 1.5 / E))
+        assert o.adk_rate(E) == pytest.approx(want, rel=1e-12)
+    # the barrier-suppression limit of Cu
+    assert k["S"] * xi ** 1.5 == pytest.approx(32.21, abs=0.01)
