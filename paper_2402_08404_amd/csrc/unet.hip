@@ -156,6 +156,119 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs p) {
 }
 
 // ---------------------------------------------------------------------------
+// 3x3x3 convolution (forward, or input gradient with flip) with the input
+// tile in LDS. A block owns an output tile of 32 x 4 x 2 voxels (x, y, z):
+// 256 GEMM rows = 16 M-tiles of 16 consecutive x voxels, wave w taking
+// M-tiles w, w+4, w+8, w+12, and all N output channels. The input channels
+// are taken in chunks of CH = min(cin, 32): for each chunk the tile with a
+// one-voxel halo (34 x 6 x 4 voxels x CH channels, bf16, zero outside the
+// volume) is staged in LDS, then all 27 taps of the chunk are reduced; an A
+// fragment is one 16-byte LDS read (8 channels of one voxel at the tap's
+// offset), a B fragment one 16-byte read of the packed weights (k = tap cin +
+// channel), shared by the wave's four M-tiles.
+constexpr int kTX = 32, kTY = 4, kTZ = 2;
+constexpr int kHX = kTX + 2, kHY = kTY + 2, kHZ = kTZ + 2;
+constexpr int kHalo = kHX * kHY * kHZ;  // 816 voxels
+constexpr int kChunk = 32;               // input channels per staged chunk
+
+__host__ __device__ inline int conv3_tiles(const Geo& g) {
+    return ((g.W + kTX - 1) / kTX) * ((g.H + kTY - 1) / kTY) * ((g.D + kTZ - 1) / kTZ) * g.B;
+}
+
+template <int NB>
+__global__ __launch_bounds__(256) void k_conv3_lds(ConvArgs p) {
+    __shared__ __align__(16) bf16_t tile[kHalo * kChunk];
+    const int cin = p.ca + p.cb;
+    const int CH = cin < kChunk ? cin : kChunk;
+    const Geo& g = p.g;
+    const int ntx = (g.W + kTX - 1) / kTX, nty = (g.H + kTY - 1) / kTY, ntz = (g.D + kTZ - 1) / kTZ;
+    int bid = blockIdx.x;
+    const int tx = bid % ntx;
+    bid /= ntx;
+    const int ty = bid % nty;
+    bid /= nty;
+    const int tz = bid % ntz;
+    const int bsm = bid / ntz;
+    const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r16 = lane & 15, kg = 8 * (lane >> 4);
+    f32x4 acc[4][NB];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[q][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const int c8n = CH >> 3;
+    const int kspan = 27 * CH;  // reduction length of one chunk
+    for (int c0 = 0; c0 < cin; c0 += CH) {
+        if (c0) __syncthreads();  // the previous chunk's reads are done
+        for (int e = threadIdx.x; e < kHalo * c8n; e += blockDim.x) {
+            const int vox = e / c8n, c8 = (e - vox * c8n) * 8;
+            const int hx = vox % kHX, hy = (vox / kHX) % kHY, hz = vox / (kHX * kHY);
+            const int X = x0 + hx - 1, Y = y0 + hy - 1, Z = z0 + hz - 1;
+            uint4 raw = make_uint4(0, 0, 0, 0);
+            if (X >= 0 && X < g.W && Y >= 0 && Y < g.H && Z >= 0 && Z < g.D) {
+                const int64_t sv = (((int64_t)bsm * g.D + Z) * g.H + Y) * g.W + X;
+                const int ch = c0 + c8;
+                raw = ch < p.ca ? *(const uint4*)(p.a + sv * p.ca + ch) : *(const uint4*)(p.b + sv * p.cb + (ch - p.ca));
+            }
+            *(uint4*)(tile + vox * CH + c8) = raw;
+        }
+        __syncthreads();
+        for (int kc = 0; kc < kspan; kc += 32) {
+            const int kk = kc + kg;
+            const bool kv = kk < kspan;
+            const int tap = kv ? kk / CH : 0, cc = kv ? kk - tap * CH : 0;
+            const int t = p.flip ? 26 - tap : tap;
+            const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+            const int64_t kw = (int64_t)tap * cin + c0 + cc;  // column of the packed weights
+            bf16x8 bv[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                uint4 wr = *(const uint4*)(p.w + (int64_t)(nb * 16 + r16) * p.Kpad + kw);
+                bv[nb] = *(bf16x8*)&wr;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int m = wave + 4 * q;
+                const int lx = 16 * (m & 1) + r16, ly = (m >> 1) & 3, lz = m >> 3;
+                const int hv = ((lz + 1 + dz) * kHY + (ly + 1 + dy)) * kHX + (lx + 1 + dx);
+                uint4 raw = make_uint4(0, 0, 0, 0);
+                if (kv) raw = *(const uint4*)(tile + hv * CH + cc);
+                const bf16x8 av = *(bf16x8*)&raw;
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[q][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nb], acc[q][nb], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int m = wave + 4 * q;
+        const int ly = (m >> 1) & 3, lz = m >> 3;
+        const int Y = y0 + ly, Z = z0 + lz;
+        if (Y >= g.H || Z >= g.D) continue;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int co = nb * 16 + r16;
+            const float bias = p.bias ? p.bias[co] : 0.f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int X = x0 + 16 * (m & 1) + 4 * (lane >> 4) + j;
+                if (X >= g.W) continue;
+                float val = acc[q][nb][j] + bias;
+                if (p.relu) val = val > 0.f ? val : 0.f;
+                const int64_t o = (((int64_t)bsm * g.D + Z) * g.H + Y) * g.W + X;
+                if (p.out) p.out[o * p.N + co] = f2bf(val);
+                if (p.out32) {
+                    float* dst = p.out32 + o * p.N + co;
+                    *dst = p.accumulate ? *dst + val : val;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Weight gradient: dW[tap][ci][co] = sum_v A(v, tap)[ci] G[v][co] over the
 // GEMM rows v of the forward layer; split over row ranges, partials written
 // per split and summed in a fixed order afterwards.
@@ -300,12 +413,18 @@ __global__ void k_input(const float* x, int64_t n, bf16_t* t) {
     t[i * 8] = f2bf(x[i]);
 }
 
-// Head: out[v] = sum_ci y[v][ci] w[ci] + b (fp32).
+// Head: out[v] = sum_ci y[v][ci] w[ci] + b (fp32); C is a multiple of 8,
+// read 8 channels (16 bytes) at a time.
 __global__ void k_head(const bf16_t* y, int C, const float* w, const float* b, int64_t n, float* out) {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     float s = b[0];
-    for (int c = 0; c < C; ++c) s += bf2f(y[v * C + c]) * w[c];
+    for (int c = 0; c < C; c += 8) {
+        uint4 raw = *(const uint4*)(y + v * C + c);
+        const bf16_t* h = (const bf16_t*)&raw;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s += bf2f(h[j]) * w[c + j];
+    }
     out[v] = s;
 }
 
@@ -607,6 +726,19 @@ static void launch_conv(unet* u, const UnetLayer& y, const bf16_t* a, const bf16
     p.par = par;
     p.g = g;
     int64_t M = (int64_t)g.B * g.D * g.H * g.W;
+    const int cin = ca + cb;
+    // every input-channel count here is 8 or a multiple of 32 (chunks of 32)
+    if (mode == kModeSame3 && (cin < kChunk ? cin % 8 == 0 : cin % kChunk == 0)) {
+        unsigned T = (unsigned)conv3_tiles(g);
+        switch (N / 16) {
+            case 1: hipLaunchKernelGGL(k_conv3_lds<1>, dim3(T), dim3(256), 0, u->stream, p); break;
+            case 2: hipLaunchKernelGGL(k_conv3_lds<2>, dim3(T), dim3(256), 0, u->stream, p); break;
+            case 4: hipLaunchKernelGGL(k_conv3_lds<4>, dim3(T), dim3(256), 0, u->stream, p); break;
+            case 8: hipLaunchKernelGGL(k_conv3_lds<8>, dim3(T), dim3(256), 0, u->stream, p); break;
+            default: u->err = "unsupported channel count"; break;
+        }
+        return;
+    }
     unsigned G = nblk(M, 64);
     switch (N / 16) {
         case 1: hipLaunchKernelGGL(k_conv<1>, dim3(G), dim3(256), 0, u->stream, p); break;
