@@ -364,6 +364,144 @@ __global__ __launch_bounds__(256) void k_wgrad(WgradArgs p) {
     }
 }
 
+// Weight gradient with larger staged chunks (R rows) and work for every
+// wave: with at least four (ci, co) tiles the waves split the tiles; with
+// fewer, each wave takes one 32-row step of every chunk (R = 128) and the four
+// partial sums are added in wave order at the end. The next chunk's rows are
+// loaded into registers while the current chunk is reduced.
+template <int R>
+__global__ __launch_bounds__(256) void k_wgrad2(WgradArgs p) {
+    constexpr int LD = (R == 128 ? 64 : 128) + 8;  // LDS row pitch (channels + pad)
+    constexpr int IT = (R * (LD - 8) / 8 + 255) / 256;  // staged items per thread and operand (max)
+    __shared__ __align__(16) bf16_t As[R][LD];
+    __shared__ __align__(16) bf16_t Gs[R][LD];
+    const int tap = blockIdx.x % p.taps;
+    const int split = blockIdx.x / p.taps;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int cin = p.ca + p.cb;
+    const int64_t M = (int64_t)p.g.B * p.g.D * p.g.H * p.g.W;
+    int64_t r0 = (int64_t)split * p.rows_per_split, r1 = r0 + p.rows_per_split;
+    if (r1 > M) r1 = M;
+    const int cin16 = (cin + 15) / 16 * 16;  // the 8-channel input is padded with zero columns
+    const int mt = cin16 / 16, nt = p.N / 16;
+    const int ntile = mt * nt;
+    const bool split_k = R == 128 && ntile < 4;  // the reduction scratch fits the R = 128 tile
+    const int a8 = cin16 / 8, g8 = p.N / 8;
+    ConvArgs cp;
+    cp.mode = p.mode;
+    cp.flip = 0;
+    cp.par = p.par;
+    cp.g = p.g;
+    uint4 ra[IT], rg[IT];
+    auto fetch = [&](int64_t rb) {
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = threadIdx.x + it * 256;
+            uint4 va = make_uint4(0, 0, 0, 0), vg = make_uint4(0, 0, 0, 0);
+            if (e < R * a8) {
+                const int rr = e / a8, c8 = (e - rr * a8) * 8;
+                const int64_t v = rb + rr;
+                if (v < r1 && c8 < cin) {
+                    bool ok = true;
+                    const int sv = src_voxel(cp, v, tap, ok);
+                    if (ok)
+                        va = c8 < p.ca ? *(const uint4*)(p.a + (int64_t)sv * p.ca + c8)
+                                       : *(const uint4*)(p.b + (int64_t)sv * p.cb + (c8 - p.ca));
+                }
+            }
+            if (e < R * g8) {
+                const int rr = e / g8, c8 = (e - rr * g8) * 8;
+                const int64_t v = rb + rr;
+                if (v < r1) vg = *(const uint4*)(p.gr + out_voxel(cp, v) * p.N + c8);
+            }
+            ra[it] = va;
+            rg[it] = vg;
+        }
+    };
+    auto store = [&]() {
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            const int e = threadIdx.x + it * 256;
+            if (e < R * a8) {
+                const int rr = e / a8, c8 = (e - rr * a8) * 8;
+                *(uint4*)&As[rr][c8] = ra[it];
+            }
+            if (e < R * g8) {
+                const int rr = e / g8, c8 = (e - rr * g8) * 8;
+                *(uint4*)&Gs[rr][c8] = rg[it];
+            }
+        }
+    };
+    f32x4 acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    const int kg = 8 * (lane >> 4);
+    if (r0 < r1) fetch(r0);
+    for (int64_t rb = r0; rb < r1; rb += R) {
+        __syncthreads();  // the previous chunk's LDS reads are done
+        store();
+        __syncthreads();
+        if (rb + R < r1) fetch(rb + R);
+        for (int sub = split_k ? wave : 0; sub < R / 32; sub += split_k ? 4 : 1) {
+            const int kr = 32 * sub + kg;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int tile = split_k ? q : wave + 4 * q;
+                if (tile < ntile) {
+                    const int mb = tile / nt, nb = tile % nt;
+                    bf16x8 av, bv;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        bf16_t x = As[kr + j][mb * 16 + (lane & 15)];
+                        bf16_t y = Gs[kr + j][nb * 16 + (lane & 15)];
+                        av[j] = *(__bf16*)&x;
+                        bv[j] = *(__bf16*)&y;
+                    }
+                    acc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[q], 0, 0, 0);
+                }
+            }
+        }
+    }
+    float* base = p.part + ((int64_t)split * p.taps + tap) * cin * p.N;
+    if (split_k) {
+        // partial sums of the four waves, added in wave order
+        __syncthreads();
+        float* red = (float*)&As[0][0];  // 4 waves x 3 tiles x 64 lanes x 4 values
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) red[((wave * 3 + q) * 64 + lane) * 4 + j] = acc[q][j];
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                if (q >= ntile) break;
+                const int mb = q / nt, nb = q % nt;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    float v = 0.f;
+                    for (int w = 0; w < 4; ++w) v += red[((w * 3 + q) * 64 + lane) * 4 + j];
+                    const int ci = mb * 16 + 4 * (lane >> 4) + j, co = nb * 16 + (lane & 15);
+                    if (ci < cin) base[(int64_t)ci * p.N + co] = v;
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int tile = wave + 4 * q;
+            if (tile < ntile) {
+                const int mb = tile / nt, nb = tile % nt;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int ci = mb * 16 + 4 * (lane >> 4) + j, co = nb * 16 + (lane & 15);
+                    if (ci < cin) base[(int64_t)ci * p.N + co] = acc[q][j];
+                }
+            }
+        }
+    }
+}
+
 // gW[i] = sum over splits of part[s][i] (fixed order)
 __global__ void k_sum_splits(const float* part, int nsplit, int64_t n, float* gw) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -459,12 +597,15 @@ __global__ void k_head_back(const bf16_t* y, int C, const float* w, const float*
     if (threadIdx.x == 0) part[(int64_t)blockIdx.x * (C + 1) + C] = t;
 }
 
+// out[c] = sum over rows of part[r][c]: one block per column, each thread
+// adding a strided subset in row order, then a block reduction (fixed order).
 __global__ void k_sum_cols(const float* part, int nrows, int ncols, float* out) {
-    int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= ncols) return;
+    __shared__ float sh[4];
+    const int c = blockIdx.x;
     float s = 0.f;
-    for (int r = 0; r < nrows; ++r) s += part[(int64_t)r * ncols + c];
-    out[c] = s;
+    for (int r = threadIdx.x; r < nrows; r += blockDim.x) s += part[(int64_t)r * ncols + c];
+    float t = pic::block_sum(s, sh);
+    if (threadIdx.x == 0) out[c] = t;
 }
 
 // Adam (fp32 master weights).
@@ -696,7 +837,7 @@ static size_t plan_bytes(const Plan& p, int64_t vox0) {
         int64_t taps = y.mode == kModeUp2 ? 8 : y.taps;
         maxpart = std::max<int64_t>(maxpart, wgrad_splits(rows) * taps * (y.ca + y.cb) * y.cout);
     }
-    maxpart = std::max<int64_t>(maxpart, ((vox0 + 255) / 256) * 64);
+    maxpart = std::max<int64_t>(maxpart, std::max<int64_t>(((vox0 + 255) / 256) * 64, 1024 * 128));
     b += al(maxe * 2) + 2 * al(maxe * 4) + al(maxpart * 4) + 2 * al(p.nparams * 4) + 2 * al(vox0 * 4) +
          al(((vox0 + 255) / 256 + 1) * 4) + 4096;
     return b;
@@ -820,7 +961,7 @@ pic_status unet_create(const pic_unet_config* c, float* params, float* grads, vo
         maxpart = std::max<int64_t>(maxpart, wgrad_splits(rows) * taps * (y.ca + y.cb) * y.cout);
     }
     int64_t vox0 = (int64_t)batch * d * h * w;
-    maxpart = std::max<int64_t>(maxpart, ((vox0 + 255) / 256) * 64);
+    maxpart = std::max<int64_t>(maxpart, std::max<int64_t>(((vox0 + 255) / 256) * 64, 1024 * 128));
     u->G = (bf16_t*)ws_take(u, maxe * 2);
     u->gm32 = (float*)ws_take(u, maxe * 4);
     u->tmp32 = (float*)ws_take(u, maxe * 4);
@@ -893,7 +1034,11 @@ static void launch_wgrad(unet* u, const UnetLayer& l, const bf16_t* a, const bf1
     int64_t rows = (int64_t)g.B * g.D * g.H * g.W;
     int64_t ns = wgrad_splits(rows);
     w.rows_per_split = (rows + ns - 1) / ns;
-    hipLaunchKernelGGL((k_wgrad<4, 4>), dim3((unsigned)(ns * taps)), dim3(256), 0, u->stream, w);
+    const int cin16 = (l.ca + l.cb + 15) / 16 * 16;
+    if (cin16 <= 64 && l.cout <= 64)
+        hipLaunchKernelGGL(k_wgrad2<128>, dim3((unsigned)(ns * taps)), dim3(256), 0, u->stream, w);
+    else
+        hipLaunchKernelGGL(k_wgrad2<32>, dim3((unsigned)(ns * taps)), dim3(256), 0, u->stream, w);
     int64_t n = (int64_t)taps * (l.ca + l.cb) * l.cout;
     hipLaunchKernelGGL(k_sum_splits, dim3(nblk(n)), dim3(256), 0, u->stream, (const float*)u->part, (int)ns, n, dst);
 }
@@ -914,7 +1059,7 @@ pic_status unet_backward(unet* u, const float* target, double* loss) {
     int Ch = u->act_c[u->head_in];
     hipLaunchKernelGGL(k_head_back, dim3(nb0), dim3(256), 0, u->stream, (const bf16_t*)u->act[u->head_in], Ch,
                        (const float*)(u->params + u->head_w), (const float*)u->dout, n0, u->gact[u->head_in], u->part);
-    hipLaunchKernelGGL(k_sum_cols, dim3(1), dim3(256), 0, u->stream, (const float*)u->part, (int)nb0, Ch + 1,
+    hipLaunchKernelGGL(k_sum_cols, dim3(Ch + 1), dim3(256), 0, u->stream, (const float*)u->part, (int)nb0, Ch + 1,
                        u->grads + u->head_w);  // head_b follows head_w
     for (int li = (int)u->L.size() - 1; li >= 0; --li) {
         const UnetLayer& l = u->L[li];
@@ -922,10 +1067,10 @@ pic_status unet_backward(unet* u, const float* target, double* loss) {
         hipLaunchKernelGGL(k_mask, dim3(nblk(nout)), dim3(256), 0, u->stream, (const float*)u->gact[l.out],
                            (const bf16_t*)u->act[l.out], l.relu, nout, u->G, u->gm32);
         // bias
-        int nbb = 64;
+        int nbb = 1024;
         hipLaunchKernelGGL(k_bias_partial, dim3(nbb), dim3(256), 0, u->stream, (const float*)u->gm32, u->act_n[l.out],
                            l.cout, u->part);
-        hipLaunchKernelGGL(k_sum_cols, dim3(1), dim3(128), 0, u->stream, (const float*)u->part, nbb, l.cout,
+        hipLaunchKernelGGL(k_sum_cols, dim3(l.cout), dim3(256), 0, u->stream, (const float*)u->part, nbb, l.cout,
                            u->grads + l.b_off);
         const bf16_t* a = u->act[l.in_a];
         const bf16_t* b = l.in_b >= 0 ? u->act[l.in_b] : nullptr;
