@@ -174,6 +174,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-zero-solve", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned warm-start leg (training on pairs of this run, then iteration counts)")
+    ap.add_argument("--learned-pairs", type=int, default=8)
+    ap.add_argument("--learned-iters", type=int, default=100)
     ap.add_argument("--prof-steps", type=int, default=5,
                     help="steps of the profiled pass after the timed region (per-kernel HIP-event timings)")
     ap.add_argument("--unet", action="store_true",
@@ -335,6 +339,8 @@ def main():
         "alive": [int(x) for x in m1["n_alive"]],
         "events_total": [int(x) for x in m1["events"]],
     }
+    if not args.no_learned:
+        out["cg"]["learned"] = learned_leg(sim, pic, args, log)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample, args.cpu_steps, np)
@@ -397,6 +403,55 @@ def unet_main(args, log):
            "train_tflops_est": 3 * fl / trn / 1e12}
     net.close()
     print(json.dumps(out), flush=True)
+
+
+def learned_leg(sim, pic, args, log):
+    """The learned warm start on this workload: training pairs from the
+    running simulation (a tight solve, then pic_training_sample, every two
+    steps), Adam on the library's network kernels, then on a later state the
+    iterations to 1e-8 of plain CG and of MG-PCG from a zero guess, from
+    V0 phi1 and from the learned guess."""
+    import torch
+    from paper_2402_08404_amd import warmstart
+    cfg = sim.cfg
+    shape = (cfg.nz, cfg.ny, cfg.nx)
+    t0 = time.perf_counter()
+    xs, ys = [], []
+    for k in range(args.learned_pairs):
+        if k:
+            sim.step(2, pic.STEP_FULL)
+        sim.solve(solver=pic.PIC_SOLVER_MGCG, guess=pic.PIC_GUESS_PREVIOUS, rtol=1e-12, maxit=100000)
+        x = torch.empty(shape, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        pic.pic_training_sample(sim.ctx, x.data_ptr(), y.data_ptr())
+        xs.append(x)
+        ys.append(y)
+    X, Y = torch.stack(xs), torch.stack(ys)
+    net = pic.UNet(1, *shape, seed=7)
+    losses = warmstart.train(net, X, Y, iters=args.learned_iters, lr=3e-4, lr_final=5e-5)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    sim.step(3, pic.STEP_FULL)  # a state the network has not seen
+    net.sync()
+    pic.pic_set_learned_guess(sim.ctx, net.net, 2)
+    res = {}
+    for sname, solver in (("plain", pic.PIC_SOLVER_CG), ("mgcg", pic.PIC_SOLVER_MGCG)):
+        for gname, guess in (("zero", pic.PIC_GUESS_ZERO), ("laplace", pic.PIC_GUESS_LAPLACE),
+                             ("learned", pic.PIC_GUESS_LEARNED)):
+            saved = sim.phi.clone()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r = sim.solve(solver=solver, guess=guess, rtol=1e-8, maxit=200000)
+            res[f"{sname}_{gname}"] = {"iters": r["iterations"], "relres0": r["relres0"],
+                                       "ms": 1e3 * (time.perf_counter() - t1)}
+            sim.phi.copy_(saved)
+    pic.pic_set_learned_guess(sim.ctx, None)
+    net.close()
+    log(f"[bench] learned leg: {args.learned_pairs} pairs, {args.learned_iters} Adam steps, {t_train:.1f} s")
+    return {"pairs": args.learned_pairs, "adam_steps": args.learned_iters, "loss_first": losses[0],
+            "loss_last": losses[-1], "train_s": t_train, "solves": res,
+            "plain_gain_vs_zero": res["plain_zero"]["iters"] / max(res["plain_learned"]["iters"], 1)}
 
 
 def batch_main(args, log):

@@ -50,18 +50,31 @@ def collect_samples(base: W.Config, fields, per_field: int, steps_between: int, 
 
 
 def train(net: pic.UNet, X: torch.Tensor, Y: torch.Tensor, iters: int, lr: float = 1e-3, seed: int = 0,
-          log_every: int = 0, lr_final: float | None = None):
+          log_every: int = 0, lr_final: float | None = None, normalize: bool = True):
     """Adam on random mini-batches (of the network's batch size) of the pairs;
-    returns the losses of every step. With lr_final the rate decays
-    geometrically from lr to lr_final."""
+    returns the losses of every step (of the normalized targets). With
+    lr_final the rate decays geometrically from lr to lr_final. With
+    normalize the targets are divided by their RMS during training and the
+    linear head is scaled by it afterwards, so the network outputs y itself."""
     B = net.shape[0]
     rng = np.random.default_rng(seed)
+    sY = float(Y.pow(2).mean().sqrt()) if normalize else 1.0
+    if not sY > 0:
+        sY = 1.0
+    Yn = Y / sY
     losses = []
     for it in range(iters):
         idx = torch.as_tensor(rng.choice(X.shape[0], size=B, replace=X.shape[0] < B), device=X.device)
         r = lr if lr_final is None else lr * (lr_final / lr) ** (it / max(iters - 1, 1))
-        loss = net.train_step(X[idx], Y[idx], r, want_loss=True)
+        loss = net.train_step(X[idx], Yn[idx], r, want_loss=True)
         losses.append(loss)
         if log_every and it % log_every == 0:
             print(f"[warmstart] iter {it} loss {loss:.4e}", flush=True)
+    if sY != 1.0:
+        # head = last (base + 1) parameters: w[base], b
+        nh = net.cfg.base_channels + 1
+        torch.cuda.synchronize(net.device)
+        net.params[-nh:] *= sY
+        torch.cuda.synchronize(net.device)
+        net.sync()
     return losses
