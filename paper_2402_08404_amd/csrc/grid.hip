@@ -550,6 +550,97 @@ __global__ __launch_bounds__(kBlock) void k_pcg_a(PcgArgs<TP> a, const float* __
     if (threadIdx.x == 0) a.part_pq[blockIdx.x] = tsum;
 }
 
+// Pair variant of k_pcg_a for FP64 Krylov vectors and an even nx: each lane
+// owns two adjacent x nodes (16-byte loads and stores of FP64 pairs), a wave
+// covers 128 consecutive x nodes of one row, and the x neighbours of the pair
+// come from the adjacent lanes by shuffles (from memory at the ends of the
+// 128-node segment). Lanes past the grid edge compute on clamped addresses and
+// store nothing, so every lane takes part in the shuffles.
+__global__ __launch_bounds__(kBlock) void k_pcg_a2(PcgArgs<double> a, const float* __restrict__ z,
+                                                    const double* part_rz, int n_rz, int kc) {
+    DevState* s = a.s;
+    if (s->done) return;
+    const Grid& g = a.g;
+    const double rz = sum_partials_n(part_rz, n_rz);
+    const double beta = s->it == 0 ? 0.0 : rz / s->rz_prev;
+    const double* __restrict__ po = a.p_old;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int ntx = (g.nx + 127) >> 7, nty = (g.ny + 3) >> 2;
+    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+    const int bx = (int)(b % ntx);
+    const int64_t rr = b / ntx;
+    const int by = (int)(rr % nty), bz = (int)(rr / nty);
+    const int i0 = bx * 128 + 2 * lane, j = by * 4 + w;
+    const int k0 = bz * kc, k1 = k0 + kc < g.nz ? k0 + kc : g.nz;
+    const bool col = i0 < g.nx && j < g.ny;
+    const int ic = col ? i0 : 0, jc = j < g.ny ? j : g.ny - 1;
+    const int64_t pl = (int64_t)g.nx * g.ny;
+    int64_t n = (int64_t)k0 * pl + (int64_t)jc * g.nx + ic;
+    auto pv2 = [&](int64_t m) {
+        const float2 zz = *(const float2*)(z + m);
+        const double2 pp = *(const double2*)(po + m);
+        return make_double2((double)zz.x + beta * pp.x, (double)zz.y + beta * pp.y);
+    };
+    auto pv1 = [&](int64_t m) { return (double)z[m] + beta * po[m]; };
+    const double hx0 = half_at_edge(ic, g.nx), hx1 = half_at_edge(ic + 1, g.nx), hy = half_at_edge(jc, g.ny);
+    const double fz0 = hx0 * hy, fz1 = hx1 * hy;
+    const bool hasW = ic > 0, hasE = ic + 2 < g.nx;
+    const int64_t os = jc > 0 ? -(int64_t)g.nx : 0, on = jc < g.ny - 1 ? (int64_t)g.nx : 0;
+    const double ws0 = jc > 0 ? hx0 : 0.0, ws1 = jc > 0 ? hx1 : 0.0;
+    const double wn0 = jc < g.ny - 1 ? hx0 : 0.0, wn1 = jc < g.ny - 1 ? hx1 : 0.0;
+    double2 pm = pv2(k0 > 0 ? n - pl : n);
+    if (k0 == 0) pm = make_double2(0.0, 0.0);
+    double2 pc = pv2(n);
+    double pq = 0.0;
+    for (int k = k0; k < k1; ++k, n += pl) {
+        const bool up = k + 1 < g.nz;
+        double2 pp = pv2(up ? n + pl : n);
+        if (!up) pp = make_double2(0.0, 0.0);
+        const double2 ps = pv2(n + os), pn = pv2(n + on);
+        const uint16_t tt = *(const uint16_t*)(a.type + n);
+        double left = __shfl_up(pc.y, 1), right = __shfl_down(pc.x, 1);
+        if (lane == 0) left = hasW ? pv1(n - 1) : 0.0;
+        if (lane == 63) right = hasE ? pv1(n + 2) : 0.0;
+        // a free node is never on a z face: fx = hy, fy = hx
+        double acc0 = 0.0;
+        acc0 += (hasW ? hy : 0.0) * (pc.x - left);
+        acc0 += hy * (pc.x - pc.y);
+        acc0 += ws0 * (pc.x - ps.x);
+        acc0 += wn0 * (pc.x - pn.x);
+        acc0 += fz0 * (pc.x - pm.x);
+        acc0 += fz0 * (pc.x - pp.x);
+        double acc1 = 0.0;
+        acc1 += hy * (pc.y - pc.x);
+        acc1 += (hasE ? hy : 0.0) * (pc.y - right);
+        acc1 += ws1 * (pc.y - ps.y);
+        acc1 += wn1 * (pc.y - pn.y);
+        acc1 += fz1 * (pc.y - pm.y);
+        acc1 += fz1 * (pc.y - pp.y);
+        const double q0 = (tt & 0xff) == 0 ? acc0 : 0.0, q1 = (tt >> 8) == 0 ? acc1 : 0.0;
+        if (col) {
+            pq += pc.x * q0;
+            pq += pc.y * q1;
+            *(double2*)(a.p_new + n) = pc;
+            *(double2*)(a.q + n) = make_double2(q0, q1);
+        }
+        pm = pc;
+        pc = pp;
+    }
+    __shared__ double sh[kBlock / 64];
+    double tsum = block_sum(pq, sh);
+    if (threadIdx.x == 0) a.part_pq[blockIdx.x] = tsum;
+}
+
+// Grid of k_pcg_a2: 128 x 4 (x, y) tiles, kc planes per block, about
+// `target` blocks.
+static unsigned pair_grid(int nx, int ny, int nz, int target, int* kc) {
+    int64_t cols = (int64_t)((nx + 127) / 128) * ((ny + 3) / 4);
+    int64_t k = (nz * cols + target - 1) / target;
+    if (k < 1) k = 1;
+    *kc = (int)k;
+    return (unsigned)(cols * ((nz + k - 1) / k));
+}
+
 template <typename TP>
 __global__ __launch_bounds__(kBlock) void k_pcg_b(PcgArgs<TP> a, const double* part_rz, int n_rz, int n_pq) {
     DevState* s = a.s;
@@ -604,7 +695,10 @@ static int pcg_iterate(pic_ctx* c, TP* x, TP* r, TP* p0, TP* p1, TP* q, int maxi
     double* part_rz = c->partials + kPartRz;
     a.chunk = ((g.nn + kCgBlocks - 1) / kCgBlocks + kBlock - 1) / kBlock * kBlock;
     int kc = 1;
-    unsigned zb = zmarch_grid(g.nx, g.ny, g.nz, stencil_target(c), 1, &kc);
+    // FP64 vectors on a grid of even width take the pair kernel
+    const bool pair = sizeof(TP) == 8 && (g.nx % 2) == 0;
+    unsigned zb = pair ? pair_grid(g.nx, g.ny, g.nz, stencil_target(c), &kc)
+                       : zmarch_grid(g.nx, g.ny, g.nz, stencil_target(c), 1, &kc);
     if (zb > 4096) return -3;
     // one iteration: V-cycle, p update and A p, x and r update
     auto iteration = [&](TP* p_old, TP* p_new, bool timed) {
@@ -615,8 +709,12 @@ static int pcg_iterate(pic_ctx* c, TP* x, TP* r, TP* p0, TP* p1, TP* q, int maxi
         a.p_old = p_old;
         a.p_new = p_new;
         int ta = timed ? tic(c, PIC_T_CG_A) : -1;
-        hipLaunchKernelGGL(k_pcg_a<TP>, dim3(zb), dim3(kBlock), 0, c->stream, a, (const float*)z,
-                           (const double*)part_rz, n_rz, kc);
+        if (pair)
+            hipLaunchKernelGGL(k_pcg_a2, dim3(zb), dim3(kBlock), 0, c->stream, *(PcgArgs<double>*)&a,
+                               (const float*)z, (const double*)part_rz, n_rz, kc);
+        else
+            hipLaunchKernelGGL(k_pcg_a<TP>, dim3(zb), dim3(kBlock), 0, c->stream, a, (const float*)z,
+                               (const double*)part_rz, n_rz, kc);
         toc(c, ta);
         int tb = timed ? tic(c, PIC_T_CG_B) : -1;
         hipLaunchKernelGGL(k_pcg_b<TP>, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a, (const double*)part_rz, n_rz,
