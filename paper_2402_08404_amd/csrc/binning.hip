@@ -124,6 +124,19 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(SortIn in, int pass, uint
     }
 }
 
+// Per-key counts of the sorted keys (integer atomics: the counts, and so the
+// offsets, do not depend on the order of the increments). Removed particles
+// (key nkeys, sorted last) are not counted: no offset needs them.
+__global__ void k_rs_count(const uint32_t* __restrict__ keys, const DevState* st, uint32_t nkeys,
+                           uint32_t* __restrict__ cnt) {
+    int64_t n = total_elems(st);
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+        const uint32_t k = keys[p];
+        if (k < nkeys) atomicAdd(&cnt[k], 1u);
+    }
+}
+
 // off[c] = first position whose key is >= c, for c = 0 .. nkeys (binary
 // search in the sorted keys; bounded work per cell whatever the gaps).
 __global__ void k_rs_offsets(const uint32_t* __restrict__ keys, const DevState* st, uint32_t nkeys,
@@ -168,10 +181,17 @@ hipError_t radix_bins(pic_ctx* c) {
         hipLaunchKernelGGL(k_rs_scatter, dim3((unsigned)nb), dim3(kBlock), 0, c->stream, in, p, nkeys, c->rs_hist, nb,
                            kbuf[p & 1], vbuf[p & 1]);
     }
-    int64_t G = ((int64_t)nkeys + 1 + kBlock - 1) / kBlock;
-    if (G > 16384) G = 16384;
-    hipLaunchKernelGGL(k_rs_offsets, dim3((unsigned)G), dim3(kBlock), 0, c->stream, kbuf[out_idx], c->st, nkeys,
-                       c->off);
+    // off = exclusive scan of the per-key counts (keys 0 .. nkeys, the last
+    // one counting removed particles)
+    hipError_t e = launch_zero(c->off, ((size_t)nkeys + 1) * 4, c->stream);
+    if (e != hipSuccess) return e;
+    int64_t Gc = (capsum + kBlock - 1) / kBlock;
+    if (Gc > 16384) Gc = 16384;
+    if (Gc < 1) Gc = 1;
+    hipLaunchKernelGGL(k_rs_count, dim3((unsigned)Gc), dim3(kBlock), 0, c->stream, (const uint32_t*)kbuf[out_idx],
+                       (const DevState*)c->st, nkeys, c->off);
+    e = scan_u32(c, c->off, c->off, (int64_t)nkeys + 1, nullptr, nullptr, false, false);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 

@@ -33,6 +33,7 @@ struct PushArgs {
     uint32_t step;
     uint64_t seed;
     uint32_t* fi_list;
+    uint32_t* part;  // per-block partials: [block][8] = max speed bits, lost[1..4], bsi
     double fi_thr, ebsi, adk_c, adk_e, x32, dt_fs;
 };
 
@@ -75,13 +76,14 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs<T> a) {
     unsigned int lost[5] = {0, 0, 0, 0, 0};
     unsigned int bsi = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        uint32_t id = a.s.id[i];
-        if (id == kDead) {
-            a.key[i] = kDead;
-            continue;
-        }
+        // The id and the state are loaded together and free slots go through
+        // the same arithmetic (their results are not stored), so no branch
+        // separates the loads: one memory latency for the state, one for the
+        // gathered field.
+        const uint32_t id = a.s.id[i];
         T X = a.s.x[i], Y = a.s.y[i], Z = a.s.z[i];
         T VX = a.s.vx[i], VY = a.s.vy[i], VZ = a.s.vz[i];
+        const bool alive = id != kDead;
         if (MOVE) {
             if (SP != PIC_NEUTRAL) {
                 T ex, ey, ez;
@@ -89,29 +91,34 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs<T> a) {
                 VX += a.kq * ex;
                 VY += a.kq * ey;
                 VZ += a.kq * ez;
-                a.s.vx[i] = VX;
-                a.s.vy[i] = VY;
-                a.s.vz[i] = VZ;
             }
             X += VX;
             Y += VY;
             Z += VZ;
+        }
+        const double Xd = (double)X, Yd = (double)Y, Zd = (double)Z;
+        const int code = alive ? boundary_code(g, Xd, Yd, Zd) : 0;
+        const int ci = clampi((int)floor(Xd), 0, g.nx - 2);
+        const int cj = clampi((int)floor(Yd), 0, g.ny - 2);
+        const int ck = clampi((int)floor(Zd), 0, g.nz - 2);
+        const bool keep = alive && code == 0;
+        a.key[i] = keep ? cell_key(g, ci, cj, ck) : kDead;
+        if (!alive) continue;
+        if (MOVE) {
+            if (SP != PIC_NEUTRAL) {
+                a.s.vx[i] = VX;
+                a.s.vy[i] = VY;
+                a.s.vz[i] = VZ;
+            }
             a.s.x[i] = X;
             a.s.y[i] = Y;
             a.s.z[i] = Z;
         }
-        double Xd = (double)X, Yd = (double)Y, Zd = (double)Z;
-        int code = boundary_code(g, Xd, Yd, Zd);
         if (code != 0) {
             a.s.id[i] = kDead;
-            a.key[i] = kDead;
             lost[code]++;
             continue;
         }
-        int ci = clampi((int)floor(Xd), 0, g.nx - 2);
-        int cj = clampi((int)floor(Yd), 0, g.ny - 2);
-        int ck = clampi((int)floor(Zd), 0, g.nz - 2);
-        a.key[i] = cell_key(g, ci, cj, ck);
         double vx = (double)VX, vy = (double)VY, vz = (double)VZ;
         unsigned int sb = speed_bits(sqrt(vx * vx + vy * vy + vz * vz));
         smax = sb > smax ? sb : smax;
@@ -134,21 +141,56 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs<T> a) {
             if (cand) a.fi_list[p] = (uint32_t)i;
         }
     }
-    // largest speed of the species
+    // per-block partials (largest speed, removals per boundary, neutrals
+    // above the barrier-suppression field), reduced by k_push_final in block
+    // order: no device-wide atomics on shared counters
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         unsigned int v = __shfl_xor(smax, o, 64);
         smax = v > smax ? v : smax;
     }
-    if (lane_id() == 0 && smax) atomicMax(&a.st->smax_bits[SP], smax);
+    __shared__ unsigned int shm[kBlock / 64];
     __shared__ unsigned int sh[kBlock / 64];
-    for (int k = 1; k < 5; ++k) {
-        unsigned int t = block_sum(lost[k], sh);
-        if (threadIdx.x == 0 && t) atomicAdd(&a.st->absorbed[SP][k], (unsigned long long)t);
+    if (lane_id() == 0) shm[threadIdx.x >> 6] = smax;
+    unsigned int tl[5];
+#pragma unroll
+    for (int k = 1; k < 5; ++k) tl[k] = block_sum(lost[k], sh);
+    unsigned int tb = block_sum(bsi, sh);  // the block reductions synchronize, shm is complete
+    if (threadIdx.x == 0) {
+        unsigned int m = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = shm[w] > m ? shm[w] : m;
+        uint32_t* q = a.part + (int64_t)blockIdx.x * 8;
+        q[0] = m;
+        for (int k = 1; k < 5; ++k) q[k] = tl[k];
+        q[5] = tb;
     }
-    if (SP == PIC_NEUTRAL) {
-        unsigned int t = block_sum(bsi, sh);
-        if (threadIdx.x == 0 && t) atomicAdd(&a.st->bsi_count, (unsigned long long)t);
+}
+
+// Reduction of the push partials of one species (one block, block order).
+template <int SP>
+__global__ void k_push_final(DevState* st, const uint32_t* part, int nblocks) {
+    __shared__ unsigned long long sh[kBlock / 64];
+    __shared__ unsigned int shm[kBlock / 64];
+    unsigned int m = 0;
+    unsigned long long s[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+        const uint32_t* q = part + (int64_t)b * 8;
+        m = q[0] > m ? q[0] : m;
+        for (int k = 1; k < 6; ++k) s[k] += q[k];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned int v = __shfl_xor(m, o, 64);
+        m = v > m ? v : m;
+    }
+    if (lane_id() == 0) shm[threadIdx.x >> 6] = m;
+    unsigned long long t[6];
+    for (int k = 1; k < 6; ++k) t[k] = block_sum(s[k], sh);
+    if (threadIdx.x == 0) {
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = shm[w] > m ? shm[w] : m;
+        if (m > st->smax_bits[SP]) st->smax_bits[SP] = m;
+        for (int k = 1; k < 5; ++k) st->absorbed[SP][k] += t[k];
+        st->bsi_count += t[5];
     }
 }
 
@@ -846,6 +888,15 @@ static unsigned grid_for(int64_t n) {
     return (unsigned)g;
 }
 
+// Grid of the push kernels (each block ends with a few device-wide atomics,
+// so the block count stays bounded).
+static unsigned grid_push(int64_t n) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > 8192) g = 8192;
+    if (g < 1) g = 1;
+    return (unsigned)g;
+}
+
 // Cell bins (radix sort of the keys), then the deposit.
 template <typename T>
 static hipError_t bin_t(pic_ctx* c) {
@@ -886,13 +937,14 @@ static hipError_t particles_t(pic_ctx* c, bool move) {
         a.step = (uint32_t)c->step;
         a.seed = cf.seed;
         a.fi_list = c->fi_list;
+        a.part = c->push_part;
         a.fi_thr = c->fi_thr;
         a.ebsi = c->ebsi;
         a.adk_c = c->adk_c;
         a.adk_e = 2.0 * c->adk_n - 1.0;
         a.x32 = pow(cf.xi, 1.5);
         a.dt_fs = cf.dt * 1e15;
-        unsigned G = grid_for(a.s.cap);
+        unsigned G = grid_push(a.s.cap);
         int t_all = s == 0 ? tic(c, PIC_T_PUSH) : -1;
         int t_e = s == 0 ? tic(c, PIC_T_PUSH_E) : -1;
         if (move) {
@@ -905,6 +957,12 @@ static hipError_t particles_t(pic_ctx* c, bool move) {
             if (s == 2) hipLaunchKernelGGL((k_push<T, 2, false>), dim3(G), dim3(kBlock), 0, c->stream, a);
         }
         toc(c, t_e);
+        if (s == 0) hipLaunchKernelGGL(k_push_final<0>, dim3(1), dim3(kBlock), 0, c->stream, c->st,
+                                       (const uint32_t*)a.part, (int)G);
+        if (s == 1) hipLaunchKernelGGL(k_push_final<1>, dim3(1), dim3(kBlock), 0, c->stream, c->st,
+                                       (const uint32_t*)a.part, (int)G);
+        if (s == 2) hipLaunchKernelGGL(k_push_final<2>, dim3(1), dim3(kBlock), 0, c->stream, c->st,
+                                       (const uint32_t*)a.part, (int)G);
         if (s == 2) toc(c, c->push_all_handle);
         if (s == 0) c->push_all_handle = t_all;
     }

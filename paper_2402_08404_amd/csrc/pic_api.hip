@@ -109,6 +109,7 @@ size_t pic::scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[
     t->rs_hist = (uint32_t*)take(256 * ((capsum + 4095) / 4096 + 1) * 4);
     t->big = (uint32_t*)take(nc * 4);
     t->fi_list = (uint32_t*)take(cap[2] * 4);
+    t->push_part = (uint32_t*)take(8192 * 8 * 4);
     t->nflag = (uint32_t*)take(cap[2] * 4);
     t->prod_list = (uint32_t*)take(cap[2] * 4);
     t->prod_ev = (int32_t*)take(cap[2] * 4);

@@ -322,6 +322,7 @@ struct pic_ctx {
     uint32_t* rs_hist = nullptr;  // digit histograms
     uint32_t* big = nullptr;      // big-cell list (nkeys)
     uint32_t* fi_list = nullptr;  // cap neutral
+    uint32_t* push_part = nullptr;  // per-block partials of the push kernels (8192 x 8)
     uint32_t* nflag = nullptr;    // cap neutral: step+1 if the neutral had an event
     uint32_t* prod_list = nullptr;
     int32_t* prod_ev = nullptr;
