@@ -170,6 +170,8 @@ def main():
     ap.add_argument("--workload", default="gpu_scale", choices=["gpu_scale", "tiny"])
     ap.add_argument("--solver", default="mgcg", choices=["cg", "mgcg", "mixed"])
     ap.add_argument("--sort-every", type=int, default=16)
+    ap.add_argument("--step-guess", type=int, default=1, choices=[0, 1],
+                    help="step-solve guess: 0 previous potential, 1 linear extrapolation in time")
     ap.add_argument("--cpu-sample", type=int, default=3_000_000)
     ap.add_argument("--cpu-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -238,7 +240,8 @@ def main():
     tune = B.load_tuning(args.tuning).get(B.shape_key(cfg), {})
     stencil_blocks = int(tune.get("stencil_blocks", 0))
     sim = pic.Simulation(cfg, caps=caps, precision=pic.PIC_F32 if fp32 else pic.PIC_F64, solver=solver,
-                         step_rtol=1e-8, step_maxit=20000, sort_every=args.sort_every, stencil_blocks=stencil_blocks)
+                         step_rtol=1e-8, step_maxit=20000, sort_every=args.sort_every, stencil_blocks=stencil_blocks,
+                         step_guess=args.step_guess)
     log(f"[bench] init done ({time.perf_counter() - t_setup:.1f} s), generating {sum(counts)} particles")
     load = W.initial_load(cfg, counts=counts, kT_eV=kT, region=region,
                           dtype=np.float32 if fp32 else np.float64)
@@ -325,7 +328,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": [cfg.nx, cfg.ny, cfg.nz], "h_m": cfg.h,
                    "particles": list(counts), "particle_state": "fp32" if fp32 else "fp64",
-                   "poisson": f"{args.solver} fp64 rtol 1e-8, previous-step guess", "sort_every": args.sort_every,
+                   "poisson": f"{args.solver} fp64 rtol 1e-8, guess "
+                              + ("extrapolated from the two previous steps" if args.step_guess else "previous step"),
+                   "sort_every": args.sort_every,
                    "stencil_blocks": stencil_blocks or 1024},
         "roofline": roof,
         "profiled_pass_ms_per_step": {k2: tm[k2][0] / psteps for k2 in

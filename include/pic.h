@@ -73,7 +73,7 @@ typedef int32_t pic_status;
 #define PIC_STEP_PUSH 0x02     /* gather, leapfrog push, boundary removal, deposit, binning (Sec. 2.2) */
 #define PIC_STEP_DEPOSIT 0x04  /* deposit and binning at the current positions, no motion */
 #define PIC_STEP_COLLIDE 0x08  /* MCC (Eqs. colp, du, newv), field ionization (Eq. dfi), products */
-#define PIC_STEP_SOLVE 0x10    /* Poisson solve (Eq. poi) with the previous potential as guess, then the field */
+#define PIC_STEP_SOLVE 0x10    /* Poisson solve (Eq. poi) from the previous potential (or its extrapolation, cfg.step_guess), then the field */
 #define PIC_STEP_FIELD 0x20    /* node field from the current potential only */
 #define PIC_STEP_ADVANCE 0x40  /* advance the step counter */
 #define PIC_STEP_EVENTS 0x80   /* record the collision events of this step (pic_events) */
@@ -111,6 +111,8 @@ typedef struct pic_config {
     int32_t sort_every;    /* reorder particles by cell every this many collide phases (0: never) */
     int64_t id_capacity;   /* largest particle id + 1 the run may reach (0: 8 x total capacity) */
     int32_t stencil_blocks; /* about this many blocks per z-marching solver kernel (0: 1024; 64..2048) */
+    int32_t step_guess;    /* guess of the solve inside pic_step: 0 the previous potential, 1 linear
+                              extrapolation 2 phi_n - phi_{n-1} from the two previous step solves */
 } pic_config;
 
 typedef struct pic_buffers {

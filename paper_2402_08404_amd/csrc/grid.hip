@@ -920,6 +920,22 @@ int mixed_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int gues
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
+// Guess of the step solve by linear extrapolation in time: with two previous
+// step solves on record, phi <- 2 phi - phi_prev; phi_prev <- the old phi.
+__global__ void k_extrapolate(int64_t nn, int apply, double* __restrict__ phi, double* __restrict__ prev) {
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (int64_t)gridDim.x * blockDim.x) {
+        const double cur = phi[n];
+        if (apply) phi[n] = 2.0 * cur - prev[n];
+        prev[n] = cur;
+    }
+}
+
+hipError_t extrapolate_phi(pic_ctx* c, bool apply) {
+    hipLaunchKernelGGL(k_extrapolate, dim3(4096), dim3(kBlock), 0, c->stream, c->g.nn, apply ? 1 : 0,
+                       (double*)c->buf.phi, c->phi_prev);
+    return hipGetLastError();
+}
+
 // Potential at a point by trilinear interpolation (one thread).
 __global__ void k_interp(Grid g, const double* phi, double X, double Y, double Z, double* out) {
     int i = clampi((int)floor(X), 0, g.nx - 2), j = clampi((int)floor(Y), 0, g.ny - 2),

@@ -53,6 +53,7 @@ const char* check_config(const pic_config* cfg) {
     if (cfg->sort_every < 0) return "sort_every must be >= 0";
     if (cfg->stencil_blocks != 0 && (cfg->stencil_blocks < 64 || cfg->stencil_blocks > 2048))
         return "stencil_blocks must be 0 or in 64..2048";
+    if (cfg->step_guess < 0 || cfg->step_guess > 1) return "step_guess must be 0 or 1";
     if (cfg->id_capacity < 0 || cfg->id_capacity > ((int64_t)1 << 32)) return "id_capacity out of range";
     return nullptr;
 }
@@ -127,6 +128,7 @@ size_t pic::scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[
     t->cg_p0 = (double*)take(nn * 8);
     t->cg_p1 = (double*)take(nn * 8);
     t->cg_q = (double*)take(nn * 8);
+    t->phi_prev = (double*)take(nn * 8);
     t->partials = (double*)take(parts * 8);
     t->mg = take(mg_bytes(cfg));
     if (c) {
@@ -326,6 +328,7 @@ pic_status pic_inject(pic_ctx* c, const pic_particles* src, int64_t* n_added) {
         if (s == PIC_OK && n_added) *n_added = src->n;
         c->bins_valid = 0;
         c->need_sort = 1;  // order the load by cell at the next collide phase
+        c->phi_hist = 0;
         return s;
     }
     unsigned long long before = c->host_st->injected;
@@ -390,10 +393,19 @@ pic_status pic_step(pic_ctx* c, int32_t nsteps, uint32_t flags) {
             toc(c, t);
         }
         if (s == PIC_OK && (flags & PIC_STEP_SOLVE)) {
+            // guess: the previous potential, or phi_n + (phi_n - phi_{n-1})
+            // once two step solves are on record (phi_prev keeps phi_n)
+            if (c->cfg.step_guess == 1) {
+                s = hip_check(c, extrapolate_phi(c, c->phi_hist >= 2), "extrapolation");
+                if (s != PIC_OK) return s;
+            }
             s = solve(c, c->cfg.solver, PIC_GUESS_PREVIOUS, c->cfg.step_rtol, c->cfg.step_maxit, nullptr);
             if (s == PIC_E_NOT_CONVERGED) {
                 result = s;
                 s = PIC_OK;
+                c->phi_hist = 0;
+            } else if (s == PIC_OK) {
+                c->phi_hist = c->phi_hist < 2 ? c->phi_hist + 1 : 2;
             }
         } else if (s == PIC_OK && (flags & PIC_STEP_FIELD)) {
             s = hip_check(c, launch_field(c, c->buf.phi, c->buf.field), "field");
@@ -414,6 +426,7 @@ pic_status pic_solve_poisson(pic_ctx* c, int32_t solver, int32_t guess, double r
         !(rtol > 0) || maxit < 0)
         return fail(c, PIC_E_INVALID_ARG, "bad solver arguments");
     if (c->prof && c->ev_n > c->ev_max / 4) flush_timers(c);
+    c->phi_hist = 0;  // the potential no longer follows the step sequence
     return solve(c, solver, guess, rtol, maxit, info);
 }
 

@@ -354,6 +354,8 @@ struct pic_ctx {
     hipGraphExec_t pcg_exec = nullptr, mix_exec = nullptr;
     int last_iters[3] = {0, 0, 0};   // iterations of the last solve per solver (first launch chunk)
     int learn_smooth = 0;            // binomial filter passes on its output
+    double* phi_prev = nullptr;      // potential of the previous step solve (extrapolated guess)
+    int phi_hist = 0;                // consecutive step solves whose potential phi_prev / phi hold
     // host state
     pic::DevState* host_st = nullptr;  // pinned mirror
     int64_t step = 0;
@@ -379,6 +381,8 @@ inline int stencil_target(const pic_ctx* c) { return c->cfg.stencil_blocks ? c->
 size_t scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[3], char* base);
 hipError_t launch_node_types(pic_ctx* c);
 hipError_t launch_field(pic_ctx* c, const double* phi, void* field);
+// step-solve guess: phi <- 2 phi - phi_prev when apply; phi_prev <- phi
+hipError_t extrapolate_phi(pic_ctx* c, bool apply);
 hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 int cg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess, double rtol, int maxit,
              pic_solve_info* info);

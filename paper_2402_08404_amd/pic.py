@@ -47,7 +47,7 @@ class pic_config(C.Structure):
                 ("xs_el", C.POINTER(C.c_double)), ("xs_iz", C.POINTER(C.c_double)), ("xs_cx", C.POINTER(C.c_double)),
                 ("fn_rings", C.c_int32), ("fn_az", C.c_int32), ("laplace_rtol", C.c_double),
                 ("step_rtol", C.c_double), ("step_maxit", C.c_int32), ("sort_every", C.c_int32),
-                ("id_capacity", C.c_int64), ("stencil_blocks", C.c_int32)]
+                ("id_capacity", C.c_int64), ("stencil_blocks", C.c_int32), ("step_guess", C.c_int32)]
 
 
 class pic_buffers(C.Structure):
@@ -275,7 +275,7 @@ def pic_training_sample(ctx, x: int, y: int) -> float:
 
 
 def make_config(cfg: workloads.Config, precision=PIC_F64, solver=PIC_SOLVER_CG, laplace_rtol=1e-13,
-                step_rtol=1e-8, step_maxit=20000, sort_every=16, id_capacity=0, stencil_blocks=0):
+                step_rtol=1e-8, step_maxit=20000, sort_every=16, id_capacity=0, stencil_blocks=0, step_guess=0):
     keep = [np.ascontiguousarray(t, dtype=np.float64) for t in (cfg.xs_el, cfg.xs_iz, cfg.xs_cx)]
     dp = C.POINTER(C.c_double)
     c = pic_config(nx=cfg.nx, ny=cfg.ny, nz=cfg.nz, precision=precision, h=cfg.h, tip_r=cfg.tip_r,
@@ -284,7 +284,7 @@ def make_config(cfg: workloads.Config, precision=PIC_F64, solver=PIC_SOLVER_CG, 
                    xs_emax=cfg.xs_emax, xs_el=keep[0].ctypes.data_as(dp), xs_iz=keep[1].ctypes.data_as(dp),
                    xs_cx=keep[2].ctypes.data_as(dp), fn_rings=cfg.fn_rings, fn_az=cfg.fn_az,
                    laplace_rtol=laplace_rtol, step_rtol=step_rtol, step_maxit=step_maxit, sort_every=sort_every,
-                   id_capacity=id_capacity, stencil_blocks=stencil_blocks)
+                   id_capacity=id_capacity, stencil_blocks=stencil_blocks, step_guess=step_guess)
     return c, keep
 
 
