@@ -73,7 +73,7 @@ SOLVER_BYTES_PER_NODE = {
 # Device symbol of each timed kernel (for the rocprofv3 traffic summary).
 KERNEL_SYMBOLS = {
     "push_electrons": "k_push<float, 0, true>",
-    "cg_a": "k_pcg_a<double>",
+    "cg_a": "k_pcg_a2",
     "cg_b": "k_pcg_b<double>",
     "mg_first": "k_mg_fine_sweep<1, false, double>",
     "mg_restrict": "k_mg_fine_restrict<double>",
