@@ -64,8 +64,8 @@ SOLVER_BYTES_PER_NODE = {
     "cg_a": 29,           # read z (4), p_old (8), type (1); write p_new (8), q (8)
     "cg_b": 48,           # read p, x, r, q (32); write x, r (16)
     "mg_first": 13,       # read b (8), type (1); write x (4)
-    "mg_restrict": 13.5,  # read x (4), b (8), type (1); write the coarse rhs (4 per 8 nodes)
-    "mg_corr": 17.5,      # read x (4), b (8), type (1), coarse x (4 per 8 nodes); write x (4)
+    "mg_restrict": 17,    # residual: read x (4), b (8), type (1); write r (4)
+    "mg_corr": 9.5,       # prolongation: read x (4), type (1), coarse x (4 per 8 nodes); write x (4)
     "mg_last": 17,        # read x (4), b (8), type (1); write z (4)
 }
 
@@ -76,8 +76,8 @@ KERNEL_SYMBOLS = {
     "cg_a": "k_pcg_a2",
     "cg_b": "k_pcg_b<double>",
     "mg_first": "k_mg_fine_sweep<1, false, double>",
-    "mg_restrict": "k_mg_fine_restrict<double>",
-    "mg_corr": "k_mg_fine_sweep<2, false, double>",
+    "mg_restrict": "k_mg_fine_sweep<3, false, double>",
+    "mg_corr": "k_mg_prolong<true>",
     "mg_last": "k_mg_fine_sweep<0, true, double>",
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gpu_scale.json")

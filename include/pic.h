@@ -237,8 +237,8 @@ pic_status pic_events(pic_ctx* ctx, pic_event* out, int64_t cap, int64_t* n);
 #define PIC_T_DEPOSIT 11      /* tiled charge deposit kernel */
 #define PIC_T_BIN 12          /* cell bins (radix sort of the cell keys) */
 #define PIC_T_MG_FIRST 13     /* finest-level pre-smoothing kernel (two sweeps from zero) */
-#define PIC_T_MG_RESTRICT 14  /* finest-level residual restriction kernel */
-#define PIC_T_MG_CORR 15      /* finest-level coarse correction + sweep kernel */
+#define PIC_T_MG_RESTRICT 14  /* finest-level residual kernel (input of the restriction) */
+#define PIC_T_MG_CORR 15      /* finest-level prolongation of the coarse correction */
 #define PIC_T_MG_LAST 16      /* finest-level last sweep kernel (with the r.z partials) */
 #define PIC_NTIMERS 17
 

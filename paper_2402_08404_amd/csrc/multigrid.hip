@@ -1,18 +1,31 @@
 // multigrid.hip -- CG preconditioned by a multigrid V-cycle for the
 // finite-volume Poisson operator of Eq. poi.
 //
-// Hierarchy: each coarse node aggregates the (up to) 2x2x2 nodes below it;
-// the prolongation P is piecewise constant and the coarse operator is the
-// Galerkin product P^T A P, which stays a 7-point stencil on the structured
-// grid (aggregates couple only through shared faces). Nodes held at a fixed
-// potential are not unknowns and belong to no aggregate. The finest level
-// uses the operator matrix-free from the node types; coarser levels store
-// diag and the +x/+y/+z couplings per node. Smoother: damped Jacobi, the same
-// number of sweeps before and after the coarse correction, so the V-cycle is
-// a symmetric positive definite preconditioner for CG. The coarsest level
-// (at most 1024 nodes) is solved exactly with its inverse, formed once on the
-// host at set-up. The finest level runs as z-marching kernels.
+// Hierarchy: cell-centred coarsening, each coarse node standing for the (up
+// to) 2x2x2 nodes below it. The prolongation P is the cell-centred trilinear
+// interpolation (along each axis a node takes 3/4 of its own coarse node and
+// 1/4 of the next one on its side; at the grid edge all of its own), the
+// restriction is P^T and the coarse operator the Galerkin product P^T A P, a
+// stencil of at most 5x5x5 points. Nodes held at a fixed potential are not
+// unknowns; a coarse node is an unknown when one of its 2x2x2 nodes is, and
+// P has no columns for the others (the interpolated correction tends to zero
+// towards a fixed region).
+//
+// Storage of a coarse operator: the rows of P^T A P are formed in FP64 on the
+// device at set-up, rounded to FP32 and grouped on the host into classes of
+// identical rows; each node keeps a class id and the level a table of the
+// distinct rows (away from the tip and the grid faces almost every node has
+// the same row, so a sweep reads the coefficients from cache, not HBM).
+// The finest level uses the 7-point operator matrix-free from the node types
+// and runs as z-marching kernels.
+//
+// Smoother: damped Jacobi, the same number of sweeps before and after the
+// coarse correction (the first from zero), so the V-cycle is a symmetric
+// positive definite preconditioner for CG. The coarsest level (at most 1024
+// nodes) is solved exactly with its inverse, formed once on the host.
 #include <cmath>
+#include <cstring>
+#include <unordered_map>
 #include <vector>
 
 #include "pic_internal.hpp"
@@ -21,31 +34,35 @@ namespace pic {
 
 constexpr int kMgMaxLevels = 12;
 
-// Storage of every multigrid vector and coarse operator: FP32 (the V-cycle is
-// a preconditioner, so its precision decides only how good the search
+// Storage of every multigrid vector and coarse coefficient: FP32 (the V-cycle
+// is a preconditioner, so its precision decides only how good the search
 // directions are; the Krylov vectors, dot products and the convergence test
 // stay FP64). Arithmetic inside the kernels is FP64.
 typedef float mgv;
-constexpr int kMgBlocks = 1024;
-constexpr double kOmega = 6.0 / 7.0;  // damped Jacobi weight for 7-point stencils
+constexpr double kOmega = 6.0 / 7.0;    // damped Jacobi weight, 7-point finest operator
+constexpr double kOmegaC = 0.7;         // damped Jacobi weight, 125-point coarse operators
+constexpr int kTabRow = 128;            // table row: 125 coefficients, omega / D at kTabInvD
+constexpr int kTabInvD = 125;
+constexpr int kCenter = 62;             // coefficient index of the node itself
 
 struct MgLevel {
     int nx, ny, nz;
     int64_t n;
-    mgv *diag, *cx, *cy, *cz;  // levels >= 1
-    mgv *x0, *x1, *b;          // x ping-pong and right-hand side (b: levels >= 1)
+    uint32_t* id;   // levels >= 1: row class per node (class 0: no unknown, zero row)
+    uint8_t* used;  // levels >= 1: 1 where the node is an unknown
+    float* tab;     // levels >= 1: class table, kTabRow floats per class
+    int ncls;
+    mgv *x0, *x1, *b;  // iterates and right-hand side (b: levels >= 1)
 };
 
 struct MgHier {
     int nlev;
     MgLevel lv[kMgMaxLevels];
-    mgv* z[2];     // finest-level preconditioned residual (ping-pong)
-    double* part;  // partial sums
-    double* cinv;  // inverse of the coarsest operator, n x n (zero rows / columns for fixed nodes)
-    int pre, post;
-    double alpha_c;
-    int zm_kc, zr_kc;          // planes per block of the fine sweeps / the fine restriction
-    unsigned zm_blocks, zr_blocks;
+    mgv* z[2];     // finest-level iterates (ping-pong)
+    double* cinv;  // inverse of the coarsest operator, n x n (zero rows / columns for non-unknowns)
+    int pre, post; // sweeps on the coarse levels (the finest level always does two and two)
+    int zm_kc;     // planes per block of the fine sweeps
+    unsigned zm_blocks;
 };
 
 static void mg_dims(const pic_config* cfg, std::vector<int3>& dims) {
@@ -63,10 +80,10 @@ size_t mg_bytes(const pic_config* cfg) {
     mg_dims(cfg, dims);
     size_t b = 4096 + sizeof(MgHier);
     int64_t nn = (int64_t)cfg->nx * cfg->ny * cfg->nz;
-    b += 2 * nn * sizeof(mgv) + 2 * 256 + 64 * kMgBlocks * 8;
+    b += 2 * nn * sizeof(mgv) + 2 * 256;
     for (size_t l = 1; l < dims.size(); ++l) {
         int64_t n = (int64_t)dims[l].x * dims[l].y * dims[l].z;
-        b += 7 * (size_t)n * sizeof(mgv) + 7 * 256;
+        b += (size_t)n * (4 + 1 + 3 * sizeof(mgv)) + 5 * 256;
     }
     int64_t nc = (int64_t)dims.back().x * dims.back().y * dims.back().z;
     if (nc <= 1024) b += (size_t)nc * nc * 8 + 256;
@@ -76,99 +93,226 @@ size_t mg_bytes(const pic_config* cfg) {
 __device__ inline double hedge(int i, int n) { return (i == 0 || i == n - 1) ? 0.5 : 1.0; }
 
 // ---------------------------------------------------------------------------
-// Setup: coarse stencils
+// Interpolation weights
 
-// Level 1 from the matrix-free finest operator.
-__global__ void k_mg_build1(Grid g, const uint8_t* __restrict__ type, MgLevel c) {
-    int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (I >= c.n) return;
-    int Ix = (int)(I % c.nx), Iy = (int)((I / c.nx) % c.ny), Iz = (int)(I / ((int64_t)c.nx * c.ny));
-    double dg = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
-    for (int t = 0; t < 8; ++t) {
-        int i = 2 * Ix + (t & 1), j = 2 * Iy + ((t >> 1) & 1), k = 2 * Iz + ((t >> 2) & 1);
-        if (i >= g.nx || j >= g.ny || k >= g.nz) continue;
-        int64_t n = ((int64_t)k * g.ny + j) * g.nx + i;
-        if (type[n] != 0) continue;
-        double fx = hedge(j, g.ny) * hedge(k, g.nz), fy = hedge(i, g.nx) * hedge(k, g.nz),
-               fz = hedge(i, g.nx) * hedge(j, g.ny);
-        int nbi[6] = {i - 1, i + 1, i, i, i, i}, nbj[6] = {j, j, j - 1, j + 1, j, j}, nbk[6] = {k, k, k, k, k - 1, k + 1};
-        double f[6] = {fx, fx, fy, fy, fz, fz};
-        for (int d = 0; d < 6; ++d) {
-            int ii = nbi[d], jj = nbj[d], kk = nbk[d];
-            if (ii < 0 || ii >= g.nx || jj < 0 || jj >= g.ny || kk < 0 || kk >= g.nz) continue;
-            dg += f[d];  // diagonal of the fine row
-            int64_t m = ((int64_t)kk * g.ny + jj) * g.nx + ii;
-            if (type[m] != 0) continue;
-            int pi = ii / 2, pj = jj / 2, pk = kk / 2;
-            if (pi == Ix && pj == Iy && pk == Iz) dg -= f[d];       // pair inside the aggregate
-            else if (d == 1 && pi == Ix + 1) cx -= f[d];             // +x face
-            else if (d == 3 && pj == Iy + 1) cy -= f[d];             // +y face
-            else if (d == 5 && pk == Iz + 1) cz -= f[d];             // +z face
-        }
-    }
-    c.diag[I] = (mgv)dg;
-    c.cx[I] = (mgv)cx;
-    c.cy[I] = (mgv)cy;
-    c.cz[I] = (mgv)cz;
+// Along one axis, fine index f of a level with nc coarse nodes: its own
+// coarse node c0 = f / 2 with weight w0 and the neighbour on its side c1
+// (f even: c0 - 1, f odd: c0 + 1) with weight w1; without that neighbour
+// w0 = 1, w1 = 0 and c1 = c0.
+struct Interp1 {
+    int c0, c1;
+    double w0, w1;
+};
+
+__host__ __device__ inline Interp1 interp1(int f, int nc) {
+    const int own = f >> 1, o = (f & 1) ? own + 1 : own - 1;
+    const bool ok = o >= 0 && o < nc;
+    Interp1 r;
+    r.c0 = own;
+    r.c1 = ok ? o : own;
+    r.w0 = ok ? 0.75 : 1.0;
+    r.w1 = ok ? 0.25 : 0.0;
+    return r;
 }
 
-// Level l+1 from the stored stencil of level l.
-__global__ void k_mg_build(MgLevel f, MgLevel c) {
-    int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (I >= c.n) return;
-    int Ix = (int)(I % c.nx), Iy = (int)((I / c.nx) % c.ny), Iz = (int)(I / ((int64_t)c.nx * c.ny));
-    double dg = 0.0, cx = 0.0, cy = 0.0, cz = 0.0;
-    int64_t pl = (int64_t)f.nx * f.ny;
+// Weight of coarse node J in the interpolation of fine index f (one axis).
+__host__ __device__ inline double interp_w(int f, int J, int nc) {
+    const Interp1 r = interp1(f, nc);
+    return (r.c0 == J ? r.w0 : 0.0) + (r.c1 == J && r.c1 != r.c0 ? r.w1 : 0.0);
+}
+
+__device__ inline int clampi(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
+
+// ---------------------------------------------------------------------------
+// Set-up: unknowns and Galerkin rows
+
+// used[J] = 1 when one of the 2x2x2 fine nodes of J is an unknown (finest:
+// free node; coarser: used).
+template <bool FINEST>
+__global__ void k_mg_used(int fnx, int fny, int fnz, const uint8_t* __restrict__ fmask, MgLevel C) {
+    int64_t J = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (J >= C.n) return;
+    const int Jx = (int)(J % C.nx), Jy = (int)((J / C.nx) % C.ny), Jz = (int)(J / ((int64_t)C.nx * C.ny));
+    uint8_t u = 0;
     for (int t = 0; t < 8; ++t) {
-        int i = 2 * Ix + (t & 1), j = 2 * Iy + ((t >> 1) & 1), k = 2 * Iz + ((t >> 2) & 1);
-        if (i >= f.nx || j >= f.ny || k >= f.nz) continue;
-        int64_t n = ((int64_t)k * f.ny + j) * f.nx + i;
-        if (f.diag[n] == 0.0) continue;
-        dg += f.diag[n];
-        // couplings to the six neighbours (off-diagonals are <= 0)
-        double cpl[6] = {i > 0 ? f.cx[n - 1] : 0.0, f.cx[n], j > 0 ? f.cy[n - f.nx] : 0.0, f.cy[n],
-                         k > 0 ? f.cz[n - pl] : 0.0, f.cz[n]};
-        int nbi[6] = {i - 1, i + 1, i, i, i, i}, nbj[6] = {j, j, j - 1, j + 1, j, j}, nbk[6] = {k, k, k, k, k - 1, k + 1};
-        for (int d = 0; d < 6; ++d) {
-            if (cpl[d] == 0.0 || nbi[d] < 0 || nbj[d] < 0 || nbk[d] < 0) continue;
-            int pi = nbi[d] / 2, pj = nbj[d] / 2, pk = nbk[d] / 2;
-            if (pi == Ix && pj == Iy && pk == Iz) dg += cpl[d];
-            else if (d == 1 && pi == Ix + 1) cx += cpl[d];
-            else if (d == 3 && pj == Iy + 1) cy += cpl[d];
-            else if (d == 5 && pk == Iz + 1) cz += cpl[d];
+        int i = 2 * Jx + (t & 1), j = 2 * Jy + ((t >> 1) & 1), k = 2 * Jz + ((t >> 2) & 1);
+        if (i >= fnx || j >= fny || k >= fnz) continue;
+        uint8_t v = fmask[((int64_t)k * fny + j) * fnx + i];
+        if (FINEST ? v == 0 : v != 0) u = 1;
+    }
+    C.used[J] = u;
+}
+
+// Row J of P^T A P: for every unknown fine node i interpolated from J (the
+// 4x4x4 fine nodes 2J-1 .. 2J+2), P[i][J] times row i of A times P, the
+// products added to the coarse offsets K - J in [-2, 2]^3. One thread per
+// coarse node, its 125 accumulators in LDS (FP64), every row summed in the
+// same order, so nodes with identical surroundings get identical rows.
+constexpr int kGalBlock = 64;
+
+struct GalerkinFine {  // row i of the finest operator, matrix-free from the node types
+    Grid g;
+    const uint8_t* type;
+};
+
+struct GalerkinCoarse {  // row i of a coarse operator from its class table
+    MgLevel F;
+};
+
+template <typename SRC>
+__device__ inline void galerkin_row(const SRC& src, const MgLevel& C, int64_t J, double* acc);
+
+// scatter v (an entry of A P's column space at fine node (ii, jj, kk)) into
+// the accumulators of coarse row J through the interpolation of that node
+__device__ inline void gal_scatter(const MgLevel& C, int fnx, int fny, int fnz, int Jx, int Jy, int Jz, int ii, int jj,
+                                   int kk, double v, double* acc) {
+    (void)fnx;
+    (void)fny;
+    (void)fnz;
+    const Interp1 px = interp1(ii, C.nx), py = interp1(jj, C.ny), pz = interp1(kk, C.nz);
+    const int cx[2] = {px.c0, px.c1}, cy[2] = {py.c0, py.c1}, cz[2] = {pz.c0, pz.c1};
+    const double wx[2] = {px.w0, px.w1}, wy[2] = {py.w0, py.w1}, wz[2] = {pz.w0, pz.w1};
+    for (int a = 0; a < 2; ++a) {
+        if (wz[a] == 0.0) continue;
+        const int dz = cz[a] - Jz;
+        for (int b = 0; b < 2; ++b) {
+            if (wy[b] == 0.0) continue;
+            const int dy = cy[b] - Jy;
+            for (int c = 0; c < 2; ++c) {
+                if (wx[c] == 0.0) continue;
+                const int dx = cx[c] - Jx;
+                if (dx < -2 || dx > 2 || dy < -2 || dy > 2 || dz < -2 || dz > 2) continue;  // not reached
+                const int64_t K = ((int64_t)cz[a] * C.ny + cy[b]) * C.nx + cx[c];
+                if (!C.used[K]) continue;
+                acc[(25 * (dz + 2) + 5 * (dy + 2) + dx + 2) * kGalBlock] += v * (wz[a] * wy[b] * wx[c]);
+            }
         }
     }
-    c.diag[I] = (mgv)dg;
-    c.cx[I] = (mgv)cx;
-    c.cy[I] = (mgv)cy;
-    c.cz[I] = (mgv)cz;
+}
+
+template <>
+__device__ inline void galerkin_row<GalerkinFine>(const GalerkinFine& src, const MgLevel& C, int64_t J, double* acc) {
+    const Grid& g = src.g;
+    const int Jx = (int)(J % C.nx), Jy = (int)((J / C.nx) % C.ny), Jz = (int)(J / ((int64_t)C.nx * C.ny));
+    for (int dk = -1; dk <= 2; ++dk) {
+        const int k = 2 * Jz + dk;
+        if (k < 0 || k >= g.nz) continue;
+        const double pz = interp_w(k, Jz, C.nz);
+        if (pz == 0.0) continue;
+        for (int dj = -1; dj <= 2; ++dj) {
+            const int j = 2 * Jy + dj;
+            if (j < 0 || j >= g.ny) continue;
+            const double py = interp_w(j, Jy, C.ny);
+            if (py == 0.0) continue;
+            for (int di = -1; di <= 2; ++di) {
+                const int i = 2 * Jx + di;
+                if (i < 0 || i >= g.nx) continue;
+                const double px = interp_w(i, Jx, C.nx);
+                if (px == 0.0) continue;
+                const int64_t n = ((int64_t)k * g.ny + j) * g.nx + i;
+                if (src.type[n] != 0) continue;
+                const double wi = px * py * pz;
+                const double fx = hedge(j, g.ny) * hedge(k, g.nz), fy = hedge(i, g.nx) * hedge(k, g.nz),
+                             fz = hedge(i, g.nx) * hedge(j, g.ny);
+                const int nbi[6] = {i - 1, i + 1, i, i, i, i}, nbj[6] = {j, j, j - 1, j + 1, j, j},
+                          nbk[6] = {k, k, k, k, k - 1, k + 1};
+                const double f[6] = {fx, fx, fy, fy, fz, fz};
+                double dg = 0.0;
+                for (int d = 0; d < 6; ++d) {
+                    const int ii = nbi[d], jj = nbj[d], kk = nbk[d];
+                    if (ii < 0 || ii >= g.nx || jj < 0 || jj >= g.ny || kk < 0 || kk >= g.nz) continue;
+                    dg += f[d];
+                }
+                gal_scatter(C, g.nx, g.ny, g.nz, Jx, Jy, Jz, i, j, k, wi * dg, acc);
+                for (int d = 0; d < 6; ++d) {
+                    const int ii = nbi[d], jj = nbj[d], kk = nbk[d];
+                    if (ii < 0 || ii >= g.nx || jj < 0 || jj >= g.ny || kk < 0 || kk >= g.nz) continue;
+                    if (src.type[((int64_t)kk * g.ny + jj) * g.nx + ii] != 0) continue;
+                    gal_scatter(C, g.nx, g.ny, g.nz, Jx, Jy, Jz, ii, jj, kk, -wi * f[d], acc);
+                }
+            }
+        }
+    }
+}
+
+template <>
+__device__ inline void galerkin_row<GalerkinCoarse>(const GalerkinCoarse& src, const MgLevel& C, int64_t J,
+                                                    double* acc) {
+    const MgLevel& F = src.F;
+    const int Jx = (int)(J % C.nx), Jy = (int)((J / C.nx) % C.ny), Jz = (int)(J / ((int64_t)C.nx * C.ny));
+    for (int dk = -1; dk <= 2; ++dk) {
+        const int k = 2 * Jz + dk;
+        if (k < 0 || k >= F.nz) continue;
+        const double pz = interp_w(k, Jz, C.nz);
+        if (pz == 0.0) continue;
+        for (int dj = -1; dj <= 2; ++dj) {
+            const int j = 2 * Jy + dj;
+            if (j < 0 || j >= F.ny) continue;
+            const double py = interp_w(j, Jy, C.ny);
+            if (py == 0.0) continue;
+            for (int di = -1; di <= 2; ++di) {
+                const int i = 2 * Jx + di;
+                if (i < 0 || i >= F.nx) continue;
+                const double px = interp_w(i, Jx, C.nx);
+                if (px == 0.0) continue;
+                const int64_t n = ((int64_t)k * F.ny + j) * F.nx + i;
+                const uint32_t cls = F.id[n];
+                if (cls == 0) continue;
+                const double wi = px * py * pz;
+                const float* row = F.tab + (size_t)cls * kTabRow;
+                for (int o = 0; o < 125; ++o) {
+                    const double a = row[o];
+                    if (a == 0.0) continue;
+                    const int ii = i + o % 5 - 2, jj = j + (o / 5) % 5 - 2, kk = k + o / 25 - 2;
+                    if (ii < 0 || ii >= F.nx || jj < 0 || jj >= F.ny || kk < 0 || kk >= F.nz) continue;  // not stored
+                    gal_scatter(C, F.nx, F.ny, F.nz, Jx, Jy, Jz, ii, jj, kk, wi * a, acc);
+                }
+            }
+        }
+    }
+}
+
+template <typename SRC>
+__global__ __launch_bounds__(kGalBlock) void k_mg_galerkin(SRC src, MgLevel C, float* __restrict__ rows) {
+    __shared__ double acc[125 * kGalBlock];
+    const int t = threadIdx.x;
+    const int64_t J = (int64_t)blockIdx.x * kGalBlock + t;
+    for (int o = 0; o < 125; ++o) acc[o * kGalBlock + t] = 0.0;
+    if (J < C.n && C.used[J]) galerkin_row<SRC>(src, C, J, acc + t);
+    if (J < C.n)
+        for (int o = 0; o < 125; ++o) rows[J * 125 + o] = (float)acc[o * kGalBlock + t];
 }
 
 // ---------------------------------------------------------------------------
-// Operator application
+// Coarse operator application
 
-// (A x)_n on a coarse level. Neighbours outside the grid are read at the node
-// itself with a zero coefficient, so all loads are unconditional.
-__device__ inline double apply_coarse(const MgLevel& L, const mgv* __restrict__ x, int64_t n, int i, int j, int k,
-                                      double xn) {
-    int64_t pl = (int64_t)L.nx * L.ny;
-    const int64_t ow = i > 0 ? -1 : 0, oe = i < L.nx - 1 ? 1 : 0;
-    const int64_t os = j > 0 ? -(int64_t)L.nx : 0, on = j < L.ny - 1 ? (int64_t)L.nx : 0;
-    const int64_t ob = k > 0 ? -pl : 0, ot = k < L.nz - 1 ? pl : 0;
-    const double cw = L.cx[n + ow], ce = L.cx[n], cs = L.cy[n + os], cn = L.cy[n], cb = L.cz[n + ob], ct = L.cz[n];
-    const double xw = x[n + ow], xe = x[n + oe], xs = x[n + os], xnn = x[n + on], xb = x[n + ob], xt = x[n + ot];
-    double s = L.diag[n] * xn;
-    s += (i > 0 ? cw : 0.0) * xw;
-    s += (i < L.nx - 1 ? ce : 0.0) * xe;
-    s += (j > 0 ? cs : 0.0) * xs;
-    s += (j < L.ny - 1 ? cn : 0.0) * xnn;
-    s += (k > 0 ? cb : 0.0) * xb;
-    s += (k < L.nz - 1 ? ct : 0.0) * xt;
+// (row . x) at node (i, j, k) of a coarse level for the class row t
+// (coefficient index 25 (dz + 2) + 5 (dy + 2) + dx + 2). Offsets outside the
+// grid have zero coefficients and are read at the clamped position, so every
+// load is unconditional.
+__device__ inline double row_dot(const MgLevel& L, const mgv* __restrict__ x, int i, int j, int k,
+                                 const float* __restrict__ t) {
+    int xs[5];
+    int64_t ys[5], zs[5];
+    const int64_t pl = (int64_t)L.nx * L.ny;
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+        xs[d] = clampi(i + d - 2, L.nx);
+        ys[d] = (int64_t)clampi(j + d - 2, L.ny) * L.nx;
+        zs[d] = (int64_t)clampi(k + d - 2, L.nz) * pl;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int dz = 0; dz < 5; ++dz) {
+#pragma unroll
+        for (int dy = 0; dy < 5; ++dy) {
+            const mgv* r = x + zs[dz] + ys[dy];
+#pragma unroll
+            for (int dx = 0; dx < 5; ++dx) s += (double)t[25 * dz + 5 * dy + dx] * (double)r[xs[dx]];
+        }
+    }
     return s;
 }
-
-// ---------------------------------------------------------------------------
-// Smoothing, restriction, prolongation
 
 struct MgArgs {
     Grid g;
@@ -205,83 +349,100 @@ __global__ void k_mg_test(MgArgs a, int cg_blocks) {
     }
 }
 
-// First sweep from x = 0 on a coarse level: x = omega D^-1 b.
-// (The small coarse-level kernels issue their loads before testing whether
-// the solve is done, so the two latencies overlap.)
+// First sweep from x = 0 on a coarse level: x = omega D^-1 b (zero where
+// there is no unknown: its table row holds omega / D = 0).
 __global__ __launch_bounds__(kBlock) void k_mg_first(MgArgs a, MgLevel L) {
-    DevState* s = a.s;
     int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= L.n) return;
-    const double d = L.diag[n], bn = L.b[n];
-    if (s->done) return;
-    L.x0[n] = (mgv)(d == 0.0 ? 0.0 : kOmega * bn / d);
-}
-
-// One damped Jacobi sweep on a coarse level, xo = xi + omega D^-1 (b - A xi),
-// optionally adding the prolonged coarse correction alpha_c P xc to xi first
-// (applied to every value read, so no separate pass is needed).
-__global__ __launch_bounds__(kBlock) void k_mg_jacobi(MgArgs a, MgLevel L, const mgv* __restrict__ xi,
-                                                       mgv* __restrict__ xo, const mgv* __restrict__ xc, MgLevel C,
-                                                       double alpha_c) {
-    DevState* s = a.s;
-    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= L.n) return;
-    int i = (int)(n % L.nx), j = (int)((n / L.nx) % L.ny), k = (int)(n / ((int64_t)L.nx * L.ny));
-    auto val = [&](int64_t m, int ii, int jj, int kk) -> double {
-        double v = xi[m];
-        if (xc) v += alpha_c * (double)xc[((int64_t)(kk / 2) * C.ny + jj / 2) * C.nx + ii / 2];
-        return v;
-    };
-    int64_t pl = (int64_t)L.nx * L.ny;
-    // neighbours outside the grid are read at the node itself, zero coefficient
-    const int iw = i > 0 ? i - 1 : i, ie = i < L.nx - 1 ? i + 1 : i;
-    const int js = j > 0 ? j - 1 : j, jn = j < L.ny - 1 ? j + 1 : j;
-    const int kb = k > 0 ? k - 1 : k, kt = k < L.nz - 1 ? k + 1 : k;
-    const int64_t ow = iw - i, oe = ie - i, os = (int64_t)(js - j) * L.nx, on = (int64_t)(jn - j) * L.nx;
-    const int64_t ob = (int64_t)(kb - k) * pl, ot = (int64_t)(kt - k) * pl;
-    const double d = L.diag[n], bn = L.b[n];
-    const double cw = L.cx[n + ow], ce = L.cx[n], cs = L.cy[n + os], cn = L.cy[n], cb = L.cz[n + ob], ct = L.cz[n];
-    const double xn = val(n, i, j, k);
-    const double xw = val(n + ow, iw, j, k), xe = val(n + oe, ie, j, k), xs = val(n + os, i, js, k),
-                 xnn = val(n + on, i, jn, k), xb = val(n + ob, i, j, kb), xt = val(n + ot, i, j, kt);
-    if (s->done) return;
-    double sacc = d * xn;
-    sacc += (i > 0 ? cw : 0.0) * xw;
-    sacc += (i < L.nx - 1 ? ce : 0.0) * xe;
-    sacc += (j > 0 ? cs : 0.0) * xs;
-    sacc += (j < L.ny - 1 ? cn : 0.0) * xnn;
-    sacc += (k > 0 ? cb : 0.0) * xb;
-    sacc += (k < L.nz - 1 ? ct : 0.0) * xt;
-    // a node without an unknown (diag 0) stays zero
-    xo[n] = (mgv)(d == 0.0 ? 0.0 : xn + kOmega * (bn - sacc) / (d == 0.0 ? 1.0 : d));
-}
-
-// b_c = P^T (b - A x) between two coarse levels: eight consecutive threads
-// per coarse node, one per child, summed in a fixed order by lane exchanges
-// ((c0 + c1) + (c2 + c3)) + ((c4 + c5) + (c6 + c7)).
-__global__ __launch_bounds__(kBlock) void k_mg_restrict(MgArgs a, MgLevel F, const mgv* __restrict__ x, MgLevel C) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t I = gid >> 3;
-    const int t = (int)(gid & 7);
-    const bool valid = I < C.n;
-    const int64_t Ic = valid ? I : C.n - 1;
-    const int Ix = (int)(Ic % C.nx), Iy = (int)((Ic / C.nx) % C.ny), Iz = (int)(Ic / ((int64_t)C.nx * C.ny));
-    int i = 2 * Ix + (t & 1), j = 2 * Iy + ((t >> 1) & 1), k = 2 * Iz + ((t >> 2) & 1);
-    const bool in = i < F.nx && j < F.ny && k < F.nz;
-    // a child outside the grid is evaluated at the first child, weight zero
-    if (!in) {
-        i = 2 * Ix;
-        j = 2 * Iy;
-        k = 2 * Iz;
-    }
-    const int64_t n = ((int64_t)k * F.ny + j) * F.nx + i;
-    const double r = (double)F.b[n] - apply_coarse(F, x, n, i, j, k, x[n]);
-    double v = (in && F.diag[n] != (mgv)0) ? r : 0.0;
-    v += __shfl_xor(v, 1);
-    v += __shfl_xor(v, 2);
-    v += __shfl_xor(v, 4);
+    const uint32_t cls = L.id[n];
+    const double bn = L.b[n];
     if (a.s->done) return;
-    if (t == 0 && valid) C.b[I] = (mgv)v;
+    L.x0[n] = (mgv)((double)L.tab[(size_t)cls * kTabRow + kTabInvD] * bn);
+}
+
+// One damped Jacobi sweep on a coarse level, xo = xi + omega D^-1 (b - A xi);
+// with RESID the residual b - A xi instead (zero where there is no unknown).
+template <bool RESID>
+__global__ __launch_bounds__(kBlock) void k_mg_sweep(MgArgs a, MgLevel L, const mgv* __restrict__ xi,
+                                                      mgv* __restrict__ xo) {
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= L.n) return;
+    const int i = (int)(n % L.nx), j = (int)((n / L.nx) % L.ny), k = (int)(n / ((int64_t)L.nx * L.ny));
+    const uint32_t cls = L.id[n];
+    const double bn = L.b[n];
+    if (a.s->done) return;
+    const float* t = L.tab + (size_t)cls * kTabRow;
+    const double ax = row_dot(L, xi, i, j, k, t);
+    if (RESID)
+        xo[n] = (mgv)((bn - ax) * (double)(cls != 0));
+    else
+        xo[n] = (mgv)((double)xi[n] + (double)t[kTabInvD] * (bn - ax));  // class 0: xi = 0, omega / D = 0
+}
+
+// b_c = P^T r: coarse node J collects the fine nodes 2J-1 .. 2J+2 of each
+// axis with their interpolation weights (zero where J is not an unknown).
+__global__ __launch_bounds__(kBlock) void k_mg_restrict(MgArgs a, int fnx, int fny, int fnz, const mgv* __restrict__ r,
+                                                         MgLevel C) {
+    int64_t J = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (J >= C.n) return;
+    const int Jx = (int)(J % C.nx), Jy = (int)((J / C.nx) % C.ny), Jz = (int)(J / ((int64_t)C.nx * C.ny));
+    double wx[4], wy[4], wz[4];
+    int ix[4];
+    int64_t jy[4], kz[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const int fi = 2 * Jx - 1 + d, fj = 2 * Jy - 1 + d, fk = 2 * Jz - 1 + d;
+        wx[d] = (fi >= 0 && fi < fnx) ? interp_w(fi, Jx, C.nx) : 0.0;
+        wy[d] = (fj >= 0 && fj < fny) ? interp_w(fj, Jy, C.ny) : 0.0;
+        wz[d] = (fk >= 0 && fk < fnz) ? interp_w(fk, Jz, C.nz) : 0.0;
+        ix[d] = clampi(fi, fnx);
+        jy[d] = (int64_t)clampi(fj, fny) * fnx;
+        kz[d] = (int64_t)clampi(fk, fnz) * fnx * fny;
+    }
+    const uint8_t u = C.used[J];
+    double s = 0.0;
+#pragma unroll
+    for (int dz = 0; dz < 4; ++dz) {
+        double sy = 0.0;
+#pragma unroll
+        for (int dy = 0; dy < 4; ++dy) {
+            const mgv* row = r + kz[dz] + jy[dy];
+            double sx = 0.0;
+#pragma unroll
+            for (int dx = 0; dx < 4; ++dx) sx += wx[dx] * (double)row[ix[dx]];
+            sy += wy[dy] * sx;
+        }
+        s += wz[dz] * sy;
+    }
+    if (a.s->done) return;
+    C.b[J] = (mgv)(s * (double)u);
+}
+
+// xo = xi + P xc on a level of fnx x fny x fnz nodes (zero where the node is
+// not an unknown: finest level, type != 0; coarser, used == 0). xc is zero on
+// coarse nodes without an unknown, which drops P's columns for them.
+template <bool FINEST>
+__global__ __launch_bounds__(kBlock) void k_mg_prolong(MgArgs a, int fnx, int fny, int fnz,
+                                                        const uint8_t* __restrict__ fmask, const mgv* __restrict__ xi,
+                                                        mgv* __restrict__ xo, MgLevel C, const mgv* __restrict__ xc) {
+    const int64_t pl = (int64_t)fnx * fny;
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= pl * fnz) return;
+    const int i = (int)(n % fnx), j = (int)((n / fnx) % fny), k = (int)(n / pl);
+    const Interp1 px = interp1(i, C.nx), py = interp1(j, C.ny), pz = interp1(k, C.nz);
+    const int64_t cpl = (int64_t)C.nx * C.ny;
+    const int64_t z0 = (int64_t)pz.c0 * cpl, z1 = (int64_t)pz.c1 * cpl;
+    const int64_t y0 = (int64_t)py.c0 * C.nx, y1 = (int64_t)py.c1 * C.nx;
+    const double v000 = xc[z0 + y0 + px.c0], v001 = xc[z0 + y0 + px.c1], v010 = xc[z0 + y1 + px.c0],
+                 v011 = xc[z0 + y1 + px.c1], v100 = xc[z1 + y0 + px.c0], v101 = xc[z1 + y0 + px.c1],
+                 v110 = xc[z1 + y1 + px.c0], v111 = xc[z1 + y1 + px.c1];
+    const uint8_t m = fmask[n];
+    const double xv = xi[n];
+    if (a.s->done) return;
+    const double s0 = py.w0 * (px.w0 * v000 + px.w1 * v001) + py.w1 * (px.w0 * v010 + px.w1 * v011);
+    const double s1 = py.w0 * (px.w0 * v100 + px.w1 * v101) + py.w1 * (px.w0 * v110 + px.w1 * v111);
+    const bool unknown = FINEST ? m == 0 : m != 0;
+    xo[n] = (mgv)((xv + pz.w0 * s0 + pz.w1 * s1) * (double)unknown);
 }
 
 // Coarsest level: x = A^-1 b with the stored inverse, one wavefront per row.
@@ -306,32 +467,19 @@ __device__ inline double fine_diag(const Grid& g, int i, int j, int k) {
            (k > 0 ? fz : 0.0) + (k < g.nz - 1 ? fz : 0.0);
 }
 
-// Input value of a fine sweep at node m = (i, j, k):
+// Input value of a fine kernel at node m:
 //   kFineFirst: the first sweep from zero, omega b / D (b is zero on fixed nodes);
-//   kFineCorr : xi + alpha_c P xc on free nodes, zero on fixed nodes;
-//   kFinePlain: xi (zero on fixed nodes).
+//   kFinePlain, kFineResid: xi (zero on fixed nodes).
 // The diagonal of a free node does not depend on k (free nodes are never on
 // a z face), so kFineFirst takes omega / D of the node's column, cw.
-constexpr int kFinePlain = 0, kFineFirst = 1, kFineCorr = 2;
+constexpr int kFinePlain = 0, kFineFirst = 1, kFineResid = 3;
 
 template <int MODE, typename TB>
 struct FineIn {
-    const uint8_t* __restrict__ type;
     const mgv* __restrict__ xi;
     const TB* __restrict__ b;
-    const mgv* __restrict__ xc;
-    int cnx, cny;
-    double ac;
-    __device__ double operator()(int64_t m, int i, int j, int k, double cw) const {
+    __device__ double operator()(int64_t m, double cw) const {
         if (MODE == kFineFirst) return cw * (double)b[m];
-        if (MODE == kFineCorr) {
-            // all three loads unconditional and the mask applied by a product
-            // (a select lets the compiler branch around the loads)
-            const uint8_t tv = type[m];
-            const double xv = xi[m];
-            const double cv = (double)xc[((int64_t)(k >> 1) * cny + (j >> 1)) * cnx + (i >> 1)];
-            return (xv + ac * cv) * (double)(tv == 0);
-        }
         return (double)xi[m];
     }
 };
@@ -342,16 +490,16 @@ __device__ inline double col_weight(const Grid& g, int i, int j) {
     return kOmega / fine_diag(g, i, j, 1 < g.nz - 1 ? 1 : 0);
 }
 
-// One damped Jacobi sweep on the finest level; with LAST the partials of
+// One damped Jacobi sweep on the finest level (kFineFirst: two sweeps from
+// zero; kFineResid: the residual b - A xi instead); with LAST the partials of
 // r.z (b . xo) are written, one per block.
 template <int MODE, bool LAST, typename TB>
 __global__ __launch_bounds__(kBlock) void k_mg_fine_sweep(MgArgs a, const TB* __restrict__ b0, const mgv* __restrict__ xi,
-                                                           mgv* __restrict__ xo, const mgv* __restrict__ xc, MgLevel C,
-                                                           double alpha_c, int kc) {
+                                                           mgv* __restrict__ xo, int kc) {
     DevState* s = a.s;
     if (s->done) return;
     const Grid& g = a.g;
-    FineIn<MODE, TB> in{a.type, xi, b0, xc, C.nx, C.ny, alpha_c};
+    FineIn<MODE, TB> in{xi, b0};
     ZMarch t = zmarch(g.nx, g.ny, g.nz, kc);
     double rz = 0.0;
     if (t.col) {
@@ -374,15 +522,15 @@ __global__ __launch_bounds__(kBlock) void k_mg_fine_sweep(MgArgs a, const TB* __
         const int64_t ow = iw - i, oe = ie - i, os = (int64_t)(js - j) * g.nx, on = (int64_t)(jn - j) * g.nx;
         const double ww = i > 0 ? hy : 0.0, we = i < g.nx - 1 ? hy : 0.0;
         const double ws = j > 0 ? hx : 0.0, wn = j < g.ny - 1 ? hx : 0.0;
-        double vm = in(t.k0 > 0 ? n - pl : n, i, j, t.k0 > 0 ? t.k0 - 1 : t.k0, cw);
+        double vm = in(t.k0 > 0 ? n - pl : n, cw);
         if (t.k0 == 0) vm = 0.0;
-        double vc = in(n, i, j, t.k0, cw);
+        double vc = in(n, cw);
         for (int k = t.k0; k < t.k1; ++k, n += pl) {
             const bool up = k + 1 < g.nz;
-            double vp = in(up ? n + pl : n, i, j, up ? k + 1 : k, cw);
+            double vp = in(up ? n + pl : n, cw);
             if (!up) vp = 0.0;
-            const double xw = in(n + ow, iw, j, k, cwW), xe = in(n + oe, ie, j, k, cwE);
-            const double xs = in(n + os, i, js, k, cwS), xn = in(n + on, i, jn, k, cwN);
+            const double xw = in(n + ow, cwW), xe = in(n + oe, cwE);
+            const double xs = in(n + os, cwS), xn = in(n + on, cwN);
             const double bn = (double)b0[n];
             const bool fr = a.type[n] == 0;
             // a free node is never on a z face: fx = hy, fy = hx (hz = 1)
@@ -393,7 +541,8 @@ __global__ __launch_bounds__(kBlock) void k_mg_fine_sweep(MgArgs a, const TB* __
             acc += wn * (vc - xn);
             acc += fz * (vc - vm);
             acc += fz * (vc - vp);
-            const mgv out = (mgv)((vc + cw * (bn - acc)) * (double)fr);  // values are finite
+            const double v = MODE == kFineResid ? bn - acc : vc + cw * (bn - acc);
+            const mgv out = (mgv)(v * (double)fr);  // values are finite
             if (LAST) rz += bn * (double)out;
             xo[n] = out;
             vm = vc;
@@ -407,68 +556,6 @@ __global__ __launch_bounds__(kBlock) void k_mg_fine_sweep(MgArgs a, const TB* __
     }
 }
 
-// b_1 = P^T (b - A x) from the finest level (kc even, so both fine planes of
-// a coarse plane are in one block). The residuals of the two planes are added
-// in the thread, the x pair by a lane exchange and the y pair through LDS,
-// always as (even + odd).
-template <typename TB>
-__global__ __launch_bounds__(kBlock) void k_mg_fine_restrict(MgArgs a, const TB* __restrict__ b0, const mgv* __restrict__ x,
-                                                              MgLevel C, int kc) {
-    if (a.s->done) return;
-    __shared__ double sh[4][64];
-    const Grid& g = a.g;
-    ZMarch t = zmarch(g.nx, g.ny, g.nz, kc);
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    const int i = t.i, j = t.j;
-    const bool col = t.col;
-    const int64_t pl = (int64_t)g.nx * g.ny;
-    int64_t n = col ? (int64_t)t.k0 * pl + (int64_t)j * g.nx + i : 0;
-    double hx = hedge(i, g.nx), hy = hedge(j, g.ny), fz = hx * hy;
-    const int iw = i > 0 ? i - 1 : i, ie = i < g.nx - 1 ? i + 1 : i;
-    const int js = j > 0 ? j - 1 : j, jn = j < g.ny - 1 ? j + 1 : j;
-    const int64_t ow = iw - i, oe = ie - i, os = (int64_t)(js - j) * g.nx, on = (int64_t)(jn - j) * g.nx;
-    const double ww = i > 0 ? hy : 0.0, we = i < g.nx - 1 ? hy : 0.0;
-    const double ws = j > 0 ? hx : 0.0, wn = j < g.ny - 1 ? hx : 0.0;
-    double vm = (col && t.k0 > 0) ? (double)x[n - pl] : 0.0;
-    double vc = col ? (double)x[n] : 0.0;
-    double pair = 0.0;
-    for (int k = t.k0; k < t.k1; ++k, n += pl) {
-        double res = 0.0;
-        double vp = 0.0;
-        if (col) {
-            const bool up = k + 1 < g.nz;
-            vp = (double)x[up ? n + pl : n];
-            if (!up) vp = 0.0;
-            const double xw = x[n + ow], xe = x[n + oe], xs = x[n + os], xn = x[n + on];
-            const double bn = (double)b0[n];
-            const bool fr = a.type[n] == 0;
-            double acc = 0.0;
-            acc += ww * (vc - xw);
-            acc += we * (vc - xe);
-            acc += ws * (vc - xs);
-            acc += wn * (vc - xn);
-            acc += fz * (vc - vm);
-            acc += fz * (vc - vp);
-            res = fr ? bn - acc : 0.0;
-        }
-        pair += res;
-        if ((k & 1) || k == g.nz - 1) {
-            double o = __shfl_xor(pair, 1);
-            double sx = (tx & 1) ? o + pair : pair + o;
-            sh[ty][tx] = sx;
-            __syncthreads();
-            if (!(tx & 1) && !(ty & 1) && col) {
-                int64_t I = ((int64_t)(k >> 1) * C.ny + (j >> 1)) * C.nx + (i >> 1);
-                C.b[I] = (mgv)(sh[ty][tx] + sh[ty + 1][tx]);
-            }
-            __syncthreads();
-            pair = 0.0;
-        }
-        vm = vc;
-        vc = vp;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Host side
 
@@ -478,34 +565,31 @@ static unsigned mg_grid(int64_t n) {
 }
 
 // Inverse of the coarsest operator (n <= 1024) by Cholesky factorization on
-// the host; rows and columns of nodes without unknowns (diag 0) stay zero.
-static int coarsest_inverse(const MgLevel& L, const std::vector<double>& dg, const std::vector<double>& cx,
-                            const std::vector<double>& cy, const std::vector<double>& cz, std::vector<double>& inv) {
+// the host (upper triangle of the stored rows); rows and columns of nodes
+// without an unknown stay zero.
+static int coarsest_inverse(const MgLevel& L, const std::vector<float>& rows, std::vector<double>& inv) {
     const int64_t n = L.n;
     std::vector<int> act;
     std::vector<int> pos(n, -1);
     for (int64_t I = 0; I < n; ++I)
-        if (dg[I] != 0.0) {
+        if (rows[(size_t)I * 125 + kCenter] != 0.0f) {
             pos[I] = (int)act.size();
             act.push_back((int)I);
         }
     const int m = (int)act.size();
     std::vector<double> A((size_t)m * m, 0.0);
-    const int64_t pl = (int64_t)L.nx * L.ny;
     for (int r = 0; r < m; ++r) {
-        int64_t I = act[r];
-        int i = (int)(I % L.nx), j = (int)((I / L.nx) % L.ny), k = (int)(I / pl);
-        A[(size_t)r * m + r] = dg[I];
-        auto couple = [&](int64_t J, double v) {
-            if (J < 0 || J >= n || pos[J] < 0 || v == 0.0) return;
-            A[(size_t)r * m + pos[J]] = v;
-        };
-        if (i > 0) couple(I - 1, cx[I - 1]);
-        if (i < L.nx - 1) couple(I + 1, cx[I]);
-        if (j > 0) couple(I - L.nx, cy[I - L.nx]);
-        if (j < L.ny - 1) couple(I + L.nx, cy[I]);
-        if (k > 0) couple(I - pl, cz[I - pl]);
-        if (k < L.nz - 1) couple(I + pl, cz[I]);
+        const int64_t I = act[r];
+        const int i = (int)(I % L.nx), j = (int)((I / L.nx) % L.ny), k = (int)(I / ((int64_t)L.nx * L.ny));
+        for (int o = 0; o < 125; ++o) {
+            const float v = rows[(size_t)I * 125 + o];
+            if (v == 0.0f) continue;
+            const int ii = i + o % 5 - 2, jj = j + (o / 5) % 5 - 2, kk = k + o / 25 - 2;
+            if (ii < 0 || ii >= L.nx || jj < 0 || jj >= L.ny || kk < 0 || kk >= L.nz) return -3;
+            const int64_t K = ((int64_t)kk * L.ny + jj) * L.nx + ii;
+            if (pos[K] < 0) return -3;
+            A[(size_t)r * m + pos[K]] = v;
+        }
     }
     // A = R^T R (upper R in place)
     for (int c = 0; c < m; ++c) {
@@ -539,6 +623,50 @@ static int coarsest_inverse(const MgLevel& L, const std::vector<double>& dg, con
     return 0;
 }
 
+// Classes of identical rows: ids[n] (0 for the zero row of a node without an
+// unknown) and the table, kTabRow floats per class with omega / D at
+// kTabInvD.
+static void row_classes(const std::vector<float>& rows, int64_t n, double omega, std::vector<uint32_t>& ids,
+                        std::vector<float>& tab) {
+    ids.assign(n, 0);
+    tab.assign(kTabRow, 0.0f);  // class 0
+    std::unordered_map<uint64_t, std::vector<uint32_t>> seen;
+    seen.reserve(1024);
+    for (int64_t I = 0; I < n; ++I) {
+        const float* r = rows.data() + (size_t)I * 125;
+        if (r[kCenter] == 0.0f) continue;
+        uint64_t h = 1469598103934665603ull;  // FNV-1a over the 125 coefficients
+        for (int o = 0; o < 125; ++o) {
+            uint32_t u;
+            std::memcpy(&u, r + o, 4);
+            h = (h ^ u) * 1099511628211ull;
+        }
+        std::vector<uint32_t>& cands = seen[h];
+        uint32_t cls = 0;
+        for (uint32_t c : cands)
+            if (std::memcmp(tab.data() + (size_t)c * kTabRow, r, 125 * sizeof(float)) == 0) {
+                cls = c;
+                break;
+            }
+        if (cls == 0) {
+            cls = (uint32_t)(tab.size() / kTabRow);
+            tab.resize(tab.size() + kTabRow, 0.0f);
+            float* t = tab.data() + (size_t)cls * kTabRow;
+            std::memcpy(t, r, 125 * sizeof(float));
+            t[kTabInvD] = (float)(omega / (double)r[kCenter]);
+            cands.push_back(cls);
+        }
+        ids[I] = cls;
+    }
+}
+
+static void mg_release(MgHier* h) {
+    if (!h) return;
+    for (int l = 1; l < h->nlev; ++l)
+        if (h->lv[l].tab) (void)hipFree(h->lv[l].tab);
+    delete h;
+}
+
 int mg_setup(pic_ctx* c) {
     std::vector<int3> dims;
     mg_dims(&c->cfg, dims);
@@ -557,73 +685,96 @@ int mg_setup(pic_ctx* c) {
     }
     h->z[0] = (mgv*)take(nn * sizeof(mgv));
     h->z[1] = (mgv*)take(nn * sizeof(mgv));
-    h->part = (double*)take(64 * kMgBlocks * 8);
     for (int l = 0; l < h->nlev; ++l) {
         MgLevel& L = h->lv[l];
         L.nx = dims[l].x;
         L.ny = dims[l].y;
         L.nz = dims[l].z;
         L.n = (int64_t)L.nx * L.ny * L.nz;
+        L.tab = nullptr;
+        L.ncls = 0;
         if (l == 0) {
-            L.diag = L.cx = L.cy = L.cz = nullptr;
+            L.id = nullptr;
+            L.used = nullptr;
             L.x0 = h->z[0];
             L.x1 = h->z[1];
             L.b = nullptr;  // the finest right-hand side is passed to each V-cycle
             continue;
         }
-        L.diag = (mgv*)take(L.n * sizeof(mgv));
-        L.cx = (mgv*)take(L.n * sizeof(mgv));
-        L.cy = (mgv*)take(L.n * sizeof(mgv));
-        L.cz = (mgv*)take(L.n * sizeof(mgv));
+        L.id = (uint32_t*)take(L.n * 4);
+        L.used = (uint8_t*)take(L.n);
         L.x0 = (mgv*)take(L.n * sizeof(mgv));
         L.x1 = (mgv*)take(L.n * sizeof(mgv));
         L.b = (mgv*)take(L.n * sizeof(mgv));
     }
     MgLevel& Lc = h->lv[h->nlev - 1];
     h->cinv = (double*)take((size_t)Lc.n * Lc.n * 8);
-    // two Jacobi sweeps each way; the piecewise-constant prolongation leaves
-    // the coarse correction too small by about a factor 2, which the weight
-    // alpha_c = 2 restores (24 instead of 60 iterations to 1e-8 on the
-    // 128 x 128 x 512 grid)
     h->pre = 2;
     h->post = 2;
-    h->alpha_c = 2.0;
     h->zm_blocks = zmarch_grid(c->g.nx, c->g.ny, c->g.nz, stencil_target(c), 1, &h->zm_kc);
-    h->zr_blocks = zmarch_grid(c->g.nx, c->g.ny, c->g.nz, stencil_target(c), 2, &h->zr_kc);
     if (h->zm_blocks > 4096) {
         delete h;
         return -3;
     }
-    for (int l = 1; l < h->nlev; ++l) {
-        MgLevel& C = h->lv[l];
-        unsigned G = (unsigned)((C.n + kBlock - 1) / kBlock);
-        if (l == 1)
-            hipLaunchKernelGGL(k_mg_build1, dim3(G), dim3(kBlock), 0, c->stream, c->g, c->buf.node_type, C);
-        else
-            hipLaunchKernelGGL(k_mg_build, dim3(G), dim3(kBlock), 0, c->stream, h->lv[l - 1], C);
+    // Galerkin rows level by level (the largest row buffer is level 1's)
+    float* rows_d = nullptr;
+    if (hipMalloc((void**)&rows_d, (size_t)h->lv[1].n * 125 * sizeof(float)) != hipSuccess) {
+        delete h;
+        return -2;
     }
-    // exact solve on the coarsest level
-    int64_t m = Lc.n;
-    std::vector<mgv> dgf(m), cxf(m), cyf(m), czf(m);
+    std::vector<float> rows;
+    std::vector<uint32_t> ids;
+    std::vector<float> tab;
     std::vector<double> inv;
-    if (hipMemcpyAsync(dgf.data(), Lc.diag, m * sizeof(mgv), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-        hipMemcpyAsync(cxf.data(), Lc.cx, m * sizeof(mgv), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-        hipMemcpyAsync(cyf.data(), Lc.cy, m * sizeof(mgv), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-        hipMemcpyAsync(czf.data(), Lc.cz, m * sizeof(mgv), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess) {
-        delete h;
-        return -2;
+    int rc = 0;
+    for (int l = 1; l < h->nlev && rc == 0; ++l) {
+        MgLevel& F = h->lv[l - 1];
+        MgLevel& C = h->lv[l];
+        const unsigned G = mg_grid(C.n), Gg = (unsigned)((C.n + kGalBlock - 1) / kGalBlock);
+        if (l == 1) {
+            hipLaunchKernelGGL(k_mg_used<true>, dim3(G), dim3(kBlock), 0, c->stream, F.nx, F.ny, F.nz,
+                               (const uint8_t*)c->buf.node_type, C);
+            GalerkinFine src{c->g, c->buf.node_type};
+            hipLaunchKernelGGL(k_mg_galerkin<GalerkinFine>, dim3(Gg), dim3(kGalBlock), 0, c->stream, src, C, rows_d);
+        } else {
+            hipLaunchKernelGGL(k_mg_used<false>, dim3(G), dim3(kBlock), 0, c->stream, F.nx, F.ny, F.nz,
+                               (const uint8_t*)F.used, C);
+            GalerkinCoarse src{F};
+            hipLaunchKernelGGL(k_mg_galerkin<GalerkinCoarse>, dim3(Gg), dim3(kGalBlock), 0, c->stream, src, C,
+                               rows_d);
+        }
+        rows.resize((size_t)C.n * 125);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(rows.data(), rows_d, rows.size() * sizeof(float), hipMemcpyDeviceToHost, c->stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess) {
+            rc = -2;
+            break;
+        }
+        row_classes(rows, C.n, kOmegaC, ids, tab);
+        C.ncls = (int)(tab.size() / kTabRow);
+        if (hipMalloc((void**)&C.tab, tab.size() * sizeof(float)) != hipSuccess ||
+            hipMemcpyAsync(C.tab, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice, c->stream) !=
+                hipSuccess ||
+            hipMemcpyAsync(C.id, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess) {
+            rc = -2;
+            break;
+        }
+        if (l == h->nlev - 1) {
+            if (coarsest_inverse(C, rows, inv) != 0) {
+                rc = -3;
+                break;
+            }
+            if (hipMemcpyAsync(h->cinv, inv.data(), inv.size() * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+                hipStreamSynchronize(c->stream) != hipSuccess)
+                rc = -2;
+        }
     }
-    std::vector<double> dg(dgf.begin(), dgf.end()), cx(cxf.begin(), cxf.end()), cy(cyf.begin(), cyf.end()),
-        cz(czf.begin(), czf.end());
-    if (coarsest_inverse(Lc, dg, cx, cy, cz, inv) != 0) {
-        delete h;
-        return -3;
-    }
-    if (hipMemcpyAsync(h->cinv, inv.data(), inv.size() * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess) {
-        delete h;
-        return -2;
+    (void)hipFree(rows_d);
+    if (rc != 0) {
+        mg_release(h);
+        return rc;
     }
     c->mg_host = h;
     return hipGetLastError() == hipSuccess ? 0 : -2;
@@ -646,70 +797,84 @@ float* mg_vcycle(pic_ctx* c, const TB* b0, double* part_rr, double* part_bb, dou
     a.part_bb = part_bb;
     a.part_rz = part_rz;
     const int nl = h->nlev;
-    const mgv* nul = nullptr;
+    const Grid& g = c->g;
     mgv* pre_out[kMgMaxLevels];  // pre-smoothed iterate per level
     mgv* res[kMgMaxLevels];      // final iterate per level
     hipLaunchKernelGGL(k_mg_test, dim3(1), dim3(kBlock), 0, c->stream, a, cg_blocks);
-    // descending: pre-smoothing (first sweep from zero + one sweep) and restriction
-    for (int l = 0; l < nl - 1; ++l) {
+    // finest level: two sweeps from zero, the residual, its restriction
+    {
+        MgLevel& L = h->lv[0];
+        int t1 = timed ? tic(c, PIC_T_MG_FIRST) : -1;
+        hipLaunchKernelGGL((k_mg_fine_sweep<kFineFirst, false, TB>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream, a,
+                           b0, (const mgv*)nullptr, L.x0, h->zm_kc);
+        toc(c, t1);
+        int t2 = timed ? tic(c, PIC_T_MG_RESTRICT) : -1;
+        hipLaunchKernelGGL((k_mg_fine_sweep<kFineResid, false, TB>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream, a,
+                           b0, (const mgv*)L.x0, L.x1, h->zm_kc);
+        toc(c, t2);
+        hipLaunchKernelGGL(k_mg_restrict, dim3(mg_grid(h->lv[1].n)), dim3(kBlock), 0, c->stream, a, g.nx, g.ny, g.nz,
+                           (const mgv*)L.x1, h->lv[1]);
+        pre_out[0] = L.x0;
+    }
+    // coarse levels down: pre-smoothing, residual, restriction
+    for (int l = 1; l < nl - 1; ++l) {
         MgLevel& L = h->lv[l];
-        MgLevel& C = h->lv[l + 1];
-        if (l == 0) {
-            int t1 = timed ? tic(c, PIC_T_MG_FIRST) : -1;
-            hipLaunchKernelGGL((k_mg_fine_sweep<kFineFirst, false, TB>), dim3(h->zm_blocks), dim3(kBlock), 0,
-                               c->stream, a, b0, nul, L.x0, nul, C, 0.0, h->zm_kc);
-            toc(c, t1);
-            int t2 = timed ? tic(c, PIC_T_MG_RESTRICT) : -1;
-            hipLaunchKernelGGL(k_mg_fine_restrict<TB>, dim3(h->zr_blocks), dim3(kBlock), 0, c->stream, a, b0,
-                               (const mgv*)L.x0, C, h->zr_kc);
-            toc(c, t2);
-            pre_out[0] = L.x0;
-        } else {
-            hipLaunchKernelGGL(k_mg_first, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L);
-            hipLaunchKernelGGL(k_mg_jacobi, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L, (const mgv*)L.x0, L.x1,
-                               nul, C, 0.0);
-            hipLaunchKernelGGL(k_mg_restrict, dim3(mg_grid(8 * C.n)), dim3(kBlock), 0, c->stream, a, L, (const mgv*)L.x1,
-                               C);
-            pre_out[l] = L.x1;
+        hipLaunchKernelGGL(k_mg_first, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L);
+        mgv* cur = L.x0;
+        mgv* oth = L.x1;
+        for (int s = 1; s < h->pre; ++s) {
+            hipLaunchKernelGGL(k_mg_sweep<false>, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L, (const mgv*)cur,
+                               oth);
+            mgv* t = cur;
+            cur = oth;
+            oth = t;
         }
+        hipLaunchKernelGGL(k_mg_sweep<true>, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L, (const mgv*)cur, oth);
+        hipLaunchKernelGGL(k_mg_restrict, dim3(mg_grid(h->lv[l + 1].n)), dim3(kBlock), 0, c->stream, a, L.nx, L.ny,
+                           L.nz, (const mgv*)oth, h->lv[l + 1]);
+        pre_out[l] = cur;
     }
     hipLaunchKernelGGL(k_mg_coarsest, dim3((unsigned)((h->lv[nl - 1].n + 3) / 4)), dim3(kBlock), 0, c->stream, a,
                        h->lv[nl - 1], (const double*)h->cinv);
     res[nl - 1] = h->lv[nl - 1].x0;
-    // ascending: correction (fused into the first post sweep) and one more sweep
-    for (int l = nl - 2; l >= 0; --l) {
+    // coarse levels up: correction, post-smoothing
+    for (int l = nl - 2; l >= 1; --l) {
         MgLevel& L = h->lv[l];
-        MgLevel& C = h->lv[l + 1];
         mgv* xi = pre_out[l];
         mgv* xo = xi == L.x0 ? L.x1 : L.x0;
-        if (l == 0) {
-            int t1 = timed ? tic(c, PIC_T_MG_CORR) : -1;
-            hipLaunchKernelGGL((k_mg_fine_sweep<kFineCorr, false, TB>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream,
-                               a, b0, (const mgv*)xi, xo, (const mgv*)res[1], C, h->alpha_c, h->zm_kc);
-            toc(c, t1);
-            int t2 = timed ? tic(c, PIC_T_MG_LAST) : -1;
-            hipLaunchKernelGGL((k_mg_fine_sweep<kFinePlain, true, TB>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream,
-                               a, b0, (const mgv*)xo, xi, nul, C, 0.0, h->zm_kc);
-            toc(c, t2);
-        } else {
-            hipLaunchKernelGGL(k_mg_jacobi, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L, (const mgv*)xi, xo,
-                               (const mgv*)res[l + 1], C, h->alpha_c);
-            hipLaunchKernelGGL(k_mg_jacobi, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L, (const mgv*)xo, xi, nul,
-                               C, 0.0);
+        hipLaunchKernelGGL(k_mg_prolong<false>, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L.nx, L.ny, L.nz,
+                           (const uint8_t*)L.used, (const mgv*)xi, xo, h->lv[l + 1], (const mgv*)res[l + 1]);
+        for (int s = 0; s < h->post; ++s) {
+            hipLaunchKernelGGL(k_mg_sweep<false>, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L, (const mgv*)xo,
+                               xi);
+            mgv* t = xi;
+            xi = xo;
+            xo = t;
         }
-        res[l] = xi;
+        res[l] = xo;
     }
+    // finest level up: correction, two sweeps (the last with the r.z partials)
+    MgLevel& L = h->lv[0];
+    int t3 = timed ? tic(c, PIC_T_MG_CORR) : -1;
+    hipLaunchKernelGGL(k_mg_prolong<true>, dim3(mg_grid(g.nn)), dim3(kBlock), 0, c->stream, a, g.nx, g.ny, g.nz,
+                       (const uint8_t*)c->buf.node_type, (const mgv*)L.x0, L.x1, h->lv[1], (const mgv*)res[1]);
+    toc(c, t3);
+    hipLaunchKernelGGL((k_mg_fine_sweep<kFinePlain, false, TB>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream, a, b0,
+                       (const mgv*)L.x1, L.x0, h->zm_kc);
+    int t4 = timed ? tic(c, PIC_T_MG_LAST) : -1;
+    hipLaunchKernelGGL((k_mg_fine_sweep<kFinePlain, true, TB>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream, a, b0,
+                       (const mgv*)L.x0, L.x1, h->zm_kc);
+    toc(c, t4);
     *n_rz = (int)h->zm_blocks;
-    return res[0];
+    return L.x1;
 }
 
 template float* mg_vcycle<double>(pic_ctx*, const double*, double*, double*, double*, int, int*, bool);
 template float* mg_vcycle<float>(pic_ctx*, const float*, double*, double*, double*, int, int*, bool);
 
 void mg_free(pic_ctx* c) {
-    delete (MgHier*)c->mg_host;
+    mg_release((MgHier*)c->mg_host);
     c->mg_host = nullptr;
 }
-
 
 }  // namespace pic
