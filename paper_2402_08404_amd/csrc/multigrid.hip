@@ -50,7 +50,7 @@ struct MgLevel {
     int64_t n;
     uint32_t* id;   // levels >= 1: row class per node (class 0: no unknown, zero row)
     uint8_t* used;  // levels >= 1: 1 where the node is an unknown
-    float* tab;     // levels >= 1: class table, kTabRow floats per class
+    float* tab;     // levels >= 1: class table, kTabRow values per class
     int ncls;
     mgv *x0, *x1, *b;  // iterates and right-hand side (b: levels >= 1)
 };
@@ -283,37 +283,6 @@ __global__ __launch_bounds__(kGalBlock) void k_mg_galerkin(SRC src, MgLevel C, f
         for (int o = 0; o < 125; ++o) rows[J * 125 + o] = (float)acc[o * kGalBlock + t];
 }
 
-// ---------------------------------------------------------------------------
-// Coarse operator application
-
-// (row . x) at node (i, j, k) of a coarse level for the class row t
-// (coefficient index 25 (dz + 2) + 5 (dy + 2) + dx + 2). Offsets outside the
-// grid have zero coefficients and are read at the clamped position, so every
-// load is unconditional.
-__device__ inline double row_dot(const MgLevel& L, const mgv* __restrict__ x, int i, int j, int k,
-                                 const float* __restrict__ t) {
-    int xs[5];
-    int64_t ys[5], zs[5];
-    const int64_t pl = (int64_t)L.nx * L.ny;
-#pragma unroll
-    for (int d = 0; d < 5; ++d) {
-        xs[d] = clampi(i + d - 2, L.nx);
-        ys[d] = (int64_t)clampi(j + d - 2, L.ny) * L.nx;
-        zs[d] = (int64_t)clampi(k + d - 2, L.nz) * pl;
-    }
-    double s = 0.0;
-#pragma unroll
-    for (int dz = 0; dz < 5; ++dz) {
-#pragma unroll
-        for (int dy = 0; dy < 5; ++dy) {
-            const mgv* r = x + zs[dz] + ys[dy];
-#pragma unroll
-            for (int dx = 0; dx < 5; ++dx) s += (double)t[25 * dz + 5 * dy + dx] * (double)r[xs[dx]];
-        }
-    }
-    return s;
-}
-
 struct MgArgs {
     Grid g;
     const uint8_t* type;
@@ -349,46 +318,140 @@ __global__ void k_mg_test(MgArgs a, int cg_blocks) {
     }
 }
 
+// Coarse-level kernels run on a grid of (plane tiles, planes): blockIdx.y is
+// the z index, blockIdx.x * kBlock + threadIdx.x the node within the plane
+// (32-bit in-plane indices).
+struct PlaneIdx {
+    int i, j, k, p;
+    int64_t n;
+};
+
+__device__ inline bool plane_idx(int nx, int ny, PlaneIdx& q) {
+    const int pl = nx * ny;
+    q.p = (int)blockIdx.x * kBlock + (int)threadIdx.x;
+    if (q.p >= pl) return false;
+    q.k = (int)blockIdx.y;
+    q.j = q.p / nx;
+    q.i = q.p - q.j * nx;
+    q.n = (int64_t)q.k * pl + q.p;
+    return true;
+}
+
 // First sweep from x = 0 on a coarse level: x = omega D^-1 b (zero where
 // there is no unknown: its table row holds omega / D = 0).
-__global__ __launch_bounds__(kBlock) void k_mg_first(MgArgs a, MgLevel L) {
-    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= L.n) return;
-    const uint32_t cls = L.id[n];
-    const double bn = L.b[n];
+__global__ __launch_bounds__(kBlock) void k_mg_first(MgArgs a, MgLevel L, const float* __restrict__ tab) {
+    PlaneIdx q;
+    if (!plane_idx(L.nx, L.ny, q)) return;
+    const uint32_t cls = L.id[q.n];
+    const double bn = L.b[q.n];
     if (a.s->done) return;
-    L.x0[n] = (mgv)((double)L.tab[(size_t)cls * kTabRow + kTabInvD] * bn);
+    L.x0[q.n] = (mgv)((double)tab[(size_t)cls * kTabRow + kTabInvD] * bn);
+}
+
+// (row . x) at node (i, j, k) of a coarse level for the class row t
+// (coefficient index 25 (dz + 2) + 5 (dy + 2) + dx + 2). Offsets outside the
+// grid have zero coefficients and are read at the clamped position, so every
+// load is unconditional.
+__device__ inline double row_dot(const MgLevel& L, const mgv* __restrict__ x, int i, int j, int k,
+                                 const float* __restrict__ t) {
+    int xs[5], ys[5];
+    int64_t zs[5];
+    const int64_t pl = (int64_t)L.nx * L.ny;
+#pragma unroll
+    for (int d = 0; d < 5; ++d) {
+        xs[d] = clampi(i + d - 2, L.nx);
+        ys[d] = clampi(j + d - 2, L.ny) * L.nx;
+        zs[d] = (int64_t)clampi(k + d - 2, L.nz) * pl;
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int dz = 0; dz < 5; ++dz) {
+#pragma unroll
+        for (int dy = 0; dy < 5; ++dy) {
+            const mgv* r = x + zs[dz] + ys[dy];
+#pragma unroll
+            for (int dx = 0; dx < 5; ++dx) s = fma((double)t[25 * dz + 5 * dy + dx], (double)r[xs[dx]], s);
+        }
+    }
+    return s;
 }
 
 // One damped Jacobi sweep on a coarse level, xo = xi + omega D^-1 (b - A xi);
 // with RESID the residual b - A xi instead (zero where there is no unknown).
 template <bool RESID>
-__global__ __launch_bounds__(kBlock) void k_mg_sweep(MgArgs a, MgLevel L, const mgv* __restrict__ xi,
-                                                      mgv* __restrict__ xo) {
-    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= L.n) return;
-    const int i = (int)(n % L.nx), j = (int)((n / L.nx) % L.ny), k = (int)(n / ((int64_t)L.nx * L.ny));
-    const uint32_t cls = L.id[n];
-    const double bn = L.b[n];
+__global__ __launch_bounds__(kBlock) void k_mg_sweep(MgArgs a, MgLevel L, const float* __restrict__ tab,
+                                                      const mgv* __restrict__ xi, mgv* __restrict__ xo) {
+    PlaneIdx q;
+    if (!plane_idx(L.nx, L.ny, q)) return;
+    const uint32_t cls = L.id[q.n];
+    const double bn = L.b[q.n];
+    const double xn = xi[q.n];
     if (a.s->done) return;
-    const float* t = L.tab + (size_t)cls * kTabRow;
-    const double ax = row_dot(L, xi, i, j, k, t);
+    const float* t = tab + (size_t)cls * kTabRow;
+    const double ax = row_dot(L, xi, q.i, q.j, q.k, t);
     if (RESID)
-        xo[n] = (mgv)((bn - ax) * (double)(cls != 0));
+        xo[q.n] = (mgv)((bn - ax) * (double)(cls != 0));
     else
-        xo[n] = (mgv)((double)xi[n] + (double)t[kTabInvD] * (bn - ax));  // class 0: xi = 0, omega / D = 0
+        xo[q.n] = (mgv)(xn + (double)t[kTabInvD] * (bn - ax));  // class 0: xn = 0, omega / D = 0
+}
+
+// b_c = P^T r for an even fine width (fnx = 2 C.nx): each lane reads its
+// two fine nodes 2J, 2J+1 of a row as one float2 and takes 2J-1 and 2J+2
+// from the neighbouring lanes (from memory at the ends of the wavefront;
+// across a row boundary the weight is zero). Lanes past the plane work on
+// the last node and store nothing, so every lane takes part in the shuffles.
+__global__ __launch_bounds__(kBlock) void k_mg_restrict2(MgArgs a, int fnx, int fny, int fnz, const mgv* __restrict__ r,
+                                                          MgLevel C) {
+    const int pl = C.nx * C.ny;
+    int p = (int)blockIdx.x * kBlock + (int)threadIdx.x;
+    const bool valid = p < pl;
+    if (!valid) p = pl - 1;
+    const int Jz = (int)blockIdx.y, Jy = p / C.nx, Jx = p - Jy * C.nx;
+    const int lane = threadIdx.x & 63;
+    double wx[4], wy[4], wz[4];
+    int jy[4];
+    int64_t kz[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const int fi = 2 * Jx - 1 + d, fj = 2 * Jy - 1 + d, fk = 2 * Jz - 1 + d;
+        wx[d] = (fi >= 0 && fi < fnx) ? interp_w(fi, Jx, C.nx) : 0.0;
+        wy[d] = (fj >= 0 && fj < fny) ? interp_w(fj, Jy, C.ny) : 0.0;
+        wz[d] = (fk >= 0 && fk < fnz) ? interp_w(fk, Jz, C.nz) : 0.0;
+        jy[d] = clampi(fj, fny) * fnx;
+        kz[d] = (int64_t)clampi(fk, fnz) * fnx * fny;
+    }
+    const bool needL = lane == 0 && Jx > 0, needR = lane == 63 && Jx + 1 < C.nx;
+    double s = 0.0;
+#pragma unroll
+    for (int dz = 0; dz < 4; ++dz) {
+        double sy = 0.0;
+#pragma unroll
+        for (int dy = 0; dy < 4; ++dy) {
+            const mgv* row = r + kz[dz] + jy[dy];
+            const float2 pr = *(const float2*)(row + 2 * Jx);
+            float left = __shfl_up(pr.y, 1), right = __shfl_down(pr.x, 1);
+            if (needL) left = row[2 * Jx - 1];
+            if (needR) right = row[2 * Jx + 2];
+            const double sx = wx[0] * (double)left + wx[1] * (double)pr.x + wx[2] * (double)pr.y + wx[3] * (double)right;
+            sy += wy[dy] * sx;
+        }
+        s += wz[dz] * sy;
+    }
+    const uint8_t u = C.used[(int64_t)Jz * pl + p];
+    if (a.s->done) return;
+    if (valid) C.b[(int64_t)Jz * pl + p] = (mgv)(s * (double)u);
 }
 
 // b_c = P^T r: coarse node J collects the fine nodes 2J-1 .. 2J+2 of each
 // axis with their interpolation weights (zero where J is not an unknown).
 __global__ __launch_bounds__(kBlock) void k_mg_restrict(MgArgs a, int fnx, int fny, int fnz, const mgv* __restrict__ r,
                                                          MgLevel C) {
-    int64_t J = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (J >= C.n) return;
-    const int Jx = (int)(J % C.nx), Jy = (int)((J / C.nx) % C.ny), Jz = (int)(J / ((int64_t)C.nx * C.ny));
+    PlaneIdx q;
+    if (!plane_idx(C.nx, C.ny, q)) return;
+    const int Jx = q.i, Jy = q.j, Jz = q.k;
     double wx[4], wy[4], wz[4];
-    int ix[4];
-    int64_t jy[4], kz[4];
+    int ix[4], jy[4];
+    int64_t kz[4];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
         const int fi = 2 * Jx - 1 + d, fj = 2 * Jy - 1 + d, fk = 2 * Jz - 1 + d;
@@ -396,10 +459,10 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(MgArgs a, int fnx, int f
         wy[d] = (fj >= 0 && fj < fny) ? interp_w(fj, Jy, C.ny) : 0.0;
         wz[d] = (fk >= 0 && fk < fnz) ? interp_w(fk, Jz, C.nz) : 0.0;
         ix[d] = clampi(fi, fnx);
-        jy[d] = (int64_t)clampi(fj, fny) * fnx;
+        jy[d] = clampi(fj, fny) * fnx;
         kz[d] = (int64_t)clampi(fk, fnz) * fnx * fny;
     }
-    const uint8_t u = C.used[J];
+    const uint8_t u = C.used[q.n];
     double s = 0.0;
 #pragma unroll
     for (int dz = 0; dz < 4; ++dz) {
@@ -415,7 +478,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(MgArgs a, int fnx, int f
         s += wz[dz] * sy;
     }
     if (a.s->done) return;
-    C.b[J] = (mgv)(s * (double)u);
+    C.b[q.n] = (mgv)(s * (double)u);
 }
 
 // xo = xi + P xc on a level of fnx x fny x fnz nodes (zero where the node is
@@ -425,24 +488,23 @@ template <bool FINEST>
 __global__ __launch_bounds__(kBlock) void k_mg_prolong(MgArgs a, int fnx, int fny, int fnz,
                                                         const uint8_t* __restrict__ fmask, const mgv* __restrict__ xi,
                                                         mgv* __restrict__ xo, MgLevel C, const mgv* __restrict__ xc) {
-    const int64_t pl = (int64_t)fnx * fny;
-    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= pl * fnz) return;
-    const int i = (int)(n % fnx), j = (int)((n / fnx) % fny), k = (int)(n / pl);
-    const Interp1 px = interp1(i, C.nx), py = interp1(j, C.ny), pz = interp1(k, C.nz);
-    const int64_t cpl = (int64_t)C.nx * C.ny;
+    (void)fnz;
+    PlaneIdx q;
+    if (!plane_idx(fnx, fny, q)) return;
+    const Interp1 px = interp1(q.i, C.nx), py = interp1(q.j, C.ny), pz = interp1(q.k, C.nz);
+    const int cpl = C.nx * C.ny;
     const int64_t z0 = (int64_t)pz.c0 * cpl, z1 = (int64_t)pz.c1 * cpl;
-    const int64_t y0 = (int64_t)py.c0 * C.nx, y1 = (int64_t)py.c1 * C.nx;
+    const int y0 = py.c0 * C.nx, y1 = py.c1 * C.nx;
     const double v000 = xc[z0 + y0 + px.c0], v001 = xc[z0 + y0 + px.c1], v010 = xc[z0 + y1 + px.c0],
                  v011 = xc[z0 + y1 + px.c1], v100 = xc[z1 + y0 + px.c0], v101 = xc[z1 + y0 + px.c1],
                  v110 = xc[z1 + y1 + px.c0], v111 = xc[z1 + y1 + px.c1];
-    const uint8_t m = fmask[n];
-    const double xv = xi[n];
+    const uint8_t m = fmask[q.n];
+    const double xv = xi[q.n];
     if (a.s->done) return;
     const double s0 = py.w0 * (px.w0 * v000 + px.w1 * v001) + py.w1 * (px.w0 * v010 + px.w1 * v011);
     const double s1 = py.w0 * (px.w0 * v100 + px.w1 * v101) + py.w1 * (px.w0 * v110 + px.w1 * v111);
     const bool unknown = FINEST ? m == 0 : m != 0;
-    xo[n] = (mgv)((xv + pz.w0 * s0 + pz.w1 * s1) * (double)unknown);
+    xo[q.n] = (mgv)((xv + pz.w0 * s0 + pz.w1 * s1) * (double)unknown);
 }
 
 // Coarsest level: x = A^-1 b with the stored inverse, one wavefront per row.
@@ -564,6 +626,12 @@ static unsigned mg_grid(int64_t n) {
     return (unsigned)(g < 1 ? 1 : g);
 }
 
+// Grid of a coarse-level kernel over nx x ny x nz nodes (see PlaneIdx).
+static dim3 plane_grid(int nx, int ny, int nz) {
+    return dim3((unsigned)(((int64_t)nx * ny + kBlock - 1) / kBlock), (unsigned)nz);
+}
+static dim3 plane_grid(const MgLevel& L) { return plane_grid(L.nx, L.ny, L.nz); }
+
 // Inverse of the coarsest operator (n <= 1024) by Cholesky factorization on
 // the host (upper triangle of the stored rows); rows and columns of nodes
 // without an unknown stay zero.
@@ -662,8 +730,9 @@ static void row_classes(const std::vector<float>& rows, int64_t n, double omega,
 
 static void mg_release(MgHier* h) {
     if (!h) return;
-    for (int l = 1; l < h->nlev; ++l)
+    for (int l = 1; l < h->nlev; ++l) {
         if (h->lv[l].tab) (void)hipFree(h->lv[l].tab);
+    }
     delete h;
 }
 
@@ -712,7 +781,8 @@ int mg_setup(pic_ctx* c) {
     h->pre = 2;
     h->post = 2;
     h->zm_blocks = zmarch_grid(c->g.nx, c->g.ny, c->g.nz, stencil_target(c), 1, &h->zm_kc);
-    if (h->zm_blocks > 4096) {
+    // plane grids: nz in gridDim.y, the plane size in 32-bit indices
+    if (h->zm_blocks > 4096 || c->g.nz > 65535 || (int64_t)c->g.nx * c->g.ny >= ((int64_t)1 << 30)) {
         delete h;
         return -3;
     }
@@ -756,8 +826,11 @@ int mg_setup(pic_ctx* c) {
         if (hipMalloc((void**)&C.tab, tab.size() * sizeof(float)) != hipSuccess ||
             hipMemcpyAsync(C.tab, tab.data(), tab.size() * sizeof(float), hipMemcpyHostToDevice, c->stream) !=
                 hipSuccess ||
-            hipMemcpyAsync(C.id, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-            hipStreamSynchronize(c->stream) != hipSuccess) {
+            hipMemcpyAsync(C.id, ids.data(), ids.size() * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess) {
+            rc = -2;
+            break;
+        }
+        if (hipStreamSynchronize(c->stream) != hipSuccess) {
             rc = -2;
             break;
         }
@@ -800,6 +873,24 @@ float* mg_vcycle(pic_ctx* c, const TB* b0, double* part_rr, double* part_bb, dou
     const Grid& g = c->g;
     mgv* pre_out[kMgMaxLevels];  // pre-smoothed iterate per level
     mgv* res[kMgMaxLevels];      // final iterate per level
+    // Jacobi sweep (resid = false) or residual (resid = true) on coarse level L
+    auto sweep = [&](const MgLevel& L, bool resid, const mgv* xi, mgv* xo) {
+        if (resid)
+            hipLaunchKernelGGL(k_mg_sweep<true>, plane_grid(L), dim3(kBlock), 0, c->stream, a, L, (const float*)L.tab, xi,
+                               xo);
+        else
+            hipLaunchKernelGGL(k_mg_sweep<false>, plane_grid(L), dim3(kBlock), 0, c->stream, a, L, (const float*)L.tab,
+                               xi, xo);
+    };
+    // b of level l + 1 from the residual r of level l
+    auto restrict_to = [&](int l, const mgv* r) {
+        const MgLevel& F = h->lv[l];
+        const MgLevel& C = h->lv[l + 1];
+        if (F.nx % 2 == 0)
+            hipLaunchKernelGGL(k_mg_restrict2, plane_grid(C), dim3(kBlock), 0, c->stream, a, F.nx, F.ny, F.nz, r, C);
+        else
+            hipLaunchKernelGGL(k_mg_restrict, plane_grid(C), dim3(kBlock), 0, c->stream, a, F.nx, F.ny, F.nz, r, C);
+    };
     hipLaunchKernelGGL(k_mg_test, dim3(1), dim3(kBlock), 0, c->stream, a, cg_blocks);
     // finest level: two sweeps from zero, the residual, its restriction
     {
@@ -812,26 +903,24 @@ float* mg_vcycle(pic_ctx* c, const TB* b0, double* part_rr, double* part_bb, dou
         hipLaunchKernelGGL((k_mg_fine_sweep<kFineResid, false, TB>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream, a,
                            b0, (const mgv*)L.x0, L.x1, h->zm_kc);
         toc(c, t2);
-        hipLaunchKernelGGL(k_mg_restrict, dim3(mg_grid(h->lv[1].n)), dim3(kBlock), 0, c->stream, a, g.nx, g.ny, g.nz,
-                           (const mgv*)L.x1, h->lv[1]);
+        restrict_to(0, (const mgv*)L.x1);
         pre_out[0] = L.x0;
     }
     // coarse levels down: pre-smoothing, residual, restriction
     for (int l = 1; l < nl - 1; ++l) {
         MgLevel& L = h->lv[l];
-        hipLaunchKernelGGL(k_mg_first, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L);
+        const float* tab = L.tab;
+        hipLaunchKernelGGL(k_mg_first, plane_grid(L), dim3(kBlock), 0, c->stream, a, L, tab);
         mgv* cur = L.x0;
         mgv* oth = L.x1;
         for (int s = 1; s < h->pre; ++s) {
-            hipLaunchKernelGGL(k_mg_sweep<false>, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L, (const mgv*)cur,
-                               oth);
+            sweep(L, false, cur, oth);
             mgv* t = cur;
             cur = oth;
             oth = t;
         }
-        hipLaunchKernelGGL(k_mg_sweep<true>, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L, (const mgv*)cur, oth);
-        hipLaunchKernelGGL(k_mg_restrict, dim3(mg_grid(h->lv[l + 1].n)), dim3(kBlock), 0, c->stream, a, L.nx, L.ny,
-                           L.nz, (const mgv*)oth, h->lv[l + 1]);
+        sweep(L, true, cur, oth);
+        restrict_to(l, (const mgv*)oth);
         pre_out[l] = cur;
     }
     hipLaunchKernelGGL(k_mg_coarsest, dim3((unsigned)((h->lv[nl - 1].n + 3) / 4)), dim3(kBlock), 0, c->stream, a,
@@ -842,11 +931,10 @@ float* mg_vcycle(pic_ctx* c, const TB* b0, double* part_rr, double* part_bb, dou
         MgLevel& L = h->lv[l];
         mgv* xi = pre_out[l];
         mgv* xo = xi == L.x0 ? L.x1 : L.x0;
-        hipLaunchKernelGGL(k_mg_prolong<false>, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L.nx, L.ny, L.nz,
+        hipLaunchKernelGGL(k_mg_prolong<false>, plane_grid(L), dim3(kBlock), 0, c->stream, a, L.nx, L.ny, L.nz,
                            (const uint8_t*)L.used, (const mgv*)xi, xo, h->lv[l + 1], (const mgv*)res[l + 1]);
         for (int s = 0; s < h->post; ++s) {
-            hipLaunchKernelGGL(k_mg_sweep<false>, dim3(mg_grid(L.n)), dim3(kBlock), 0, c->stream, a, L, (const mgv*)xo,
-                               xi);
+            sweep(L, false, xo, xi);
             mgv* t = xi;
             xi = xo;
             xo = t;
@@ -856,7 +944,7 @@ float* mg_vcycle(pic_ctx* c, const TB* b0, double* part_rr, double* part_bb, dou
     // finest level up: correction, two sweeps (the last with the r.z partials)
     MgLevel& L = h->lv[0];
     int t3 = timed ? tic(c, PIC_T_MG_CORR) : -1;
-    hipLaunchKernelGGL(k_mg_prolong<true>, dim3(mg_grid(g.nn)), dim3(kBlock), 0, c->stream, a, g.nx, g.ny, g.nz,
+    hipLaunchKernelGGL(k_mg_prolong<true>, plane_grid(g.nx, g.ny, g.nz), dim3(kBlock), 0, c->stream, a, g.nx, g.ny, g.nz,
                        (const uint8_t*)c->buf.node_type, (const mgv*)L.x0, L.x1, h->lv[1], (const mgv*)res[1]);
     toc(c, t3);
     hipLaunchKernelGGL((k_mg_fine_sweep<kFinePlain, false, TB>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream, a, b0,
