@@ -77,7 +77,7 @@ KERNEL_SYMBOLS = {
     "cg_b": "k_pcg_b<double>",
     "mg_first": "k_mg_fine_sweep<1, false, double>",
     "mg_restrict": "k_mg_fine_sweep<3, false, double>",
-    "mg_corr": "k_mg_prolong<true>",
+    "mg_corr": "k_mg_prolong2",
     "mg_last": "k_mg_fine_sweep<0, true, double>",
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gpu_scale.json")

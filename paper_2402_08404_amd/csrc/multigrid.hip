@@ -41,8 +41,9 @@ constexpr int kMgMaxLevels = 12;
 typedef float mgv;
 constexpr double kOmega = 6.0 / 7.0;    // damped Jacobi weight, 7-point finest operator
 constexpr double kOmegaC = 0.7;         // damped Jacobi weight, 125-point coarse operators
-constexpr int kTabRow = 128;            // table row: 125 coefficients, omega / D at kTabInvD
+constexpr int kTabRow = 128;            // table row: 125 coefficients, omega / D, row sum
 constexpr int kTabInvD = 125;
+constexpr int kTabSum = 126;
 constexpr int kCenter = 62;             // coefficient index of the node itself
 
 struct MgLevel {
@@ -318,19 +319,29 @@ __global__ void k_mg_test(MgArgs a, int cg_blocks) {
     }
 }
 
-// Coarse-level kernels run on a grid of (plane tiles, planes): blockIdx.y is
-// the z index, blockIdx.x * kBlock + threadIdx.x the node within the plane
-// (32-bit in-plane indices).
+// Coarse-level kernels run on a grid of (plane tiles, planes): a block is a
+// tile of kBlock nodes of one plane (32-bit in-plane indices). The linear
+// block index is remapped so that consecutive planes run on one XCD and the
+// planes a stencil or a transfer shares stay in that XCD's L2.
 struct PlaneIdx {
     int i, j, k, p;
     int64_t n;
 };
 
+__device__ inline void plane_block(int& bx, int& bz) {
+    const uint32_t nbx = gridDim.x;
+    const uint32_t b = (uint32_t)xcd_block((int64_t)blockIdx.y * nbx + blockIdx.x, (int64_t)nbx * gridDim.y);
+    bz = (int)(b / nbx);
+    bx = (int)(b - (uint32_t)bz * nbx);
+}
+
 __device__ inline bool plane_idx(int nx, int ny, PlaneIdx& q) {
     const int pl = nx * ny;
-    q.p = (int)blockIdx.x * kBlock + (int)threadIdx.x;
+    int bx, bz;
+    plane_block(bx, bz);
+    q.p = bx * kBlock + (int)threadIdx.x;
     if (q.p >= pl) return false;
-    q.k = (int)blockIdx.y;
+    q.k = bz;
     q.j = q.p / nx;
     q.i = q.p - q.j * nx;
     q.n = (int64_t)q.k * pl + q.p;
@@ -349,31 +360,33 @@ __global__ __launch_bounds__(kBlock) void k_mg_first(MgArgs a, MgLevel L, const 
 }
 
 // (row . x) at node (i, j, k) of a coarse level for the class row t
-// (coefficient index 25 (dz + 2) + 5 (dy + 2) + dx + 2). Offsets outside the
-// grid have zero coefficients and are read at the clamped position, so every
-// load is unconditional.
-__device__ inline double row_dot(const MgLevel& L, const mgv* __restrict__ x, int i, int j, int k,
+// (coefficient index 25 (dz + 2) + 5 (dy + 2) + dx + 2), as
+// sum_o t_o (x_o - x_c) + (sum_o t_o) x_c: the differences of neighbouring
+// values are small where x is smooth, so the 125 products are accumulated in
+// FP32 without the cancellation of a plain sum; the row-sum term is FP64.
+// Offsets outside the grid have zero coefficients and are read at the
+// clamped position, so every load is unconditional (32-bit byte offsets from
+// the level's base pointer; a coarse level is far below 4 GiB).
+__device__ inline double row_dot(const MgLevel& L, const mgv* __restrict__ x, int i, int j, int k, float xc,
                                  const float* __restrict__ t) {
-    int xs[5], ys[5];
-    int64_t zs[5];
-    const int64_t pl = (int64_t)L.nx * L.ny;
+    uint32_t xs[5], rows[25];
+    const uint32_t pl = (uint32_t)(L.nx * L.ny);
 #pragma unroll
-    for (int d = 0; d < 5; ++d) {
-        xs[d] = clampi(i + d - 2, L.nx);
-        ys[d] = clampi(j + d - 2, L.ny) * L.nx;
-        zs[d] = (int64_t)clampi(k + d - 2, L.nz) * pl;
-    }
-    double s = 0.0;
+    for (int d = 0; d < 5; ++d) xs[d] = 4u * (uint32_t)clampi(i + d - 2, L.nx);
 #pragma unroll
     for (int dz = 0; dz < 5; ++dz) {
+        const uint32_t zr = (uint32_t)clampi(k + dz - 2, L.nz) * pl;
 #pragma unroll
-        for (int dy = 0; dy < 5; ++dy) {
-            const mgv* r = x + zs[dz] + ys[dy];
-#pragma unroll
-            for (int dx = 0; dx < 5; ++dx) s = fma((double)t[25 * dz + 5 * dy + dx], (double)r[xs[dx]], s);
-        }
+        for (int dy = 0; dy < 5; ++dy) rows[5 * dz + dy] = 4u * (zr + (uint32_t)(clampi(j + dy - 2, L.ny) * L.nx));
     }
-    return s;
+    const char* __restrict__ xb = (const char*)x;
+    float s = 0.0f;
+#pragma unroll
+    for (int r = 0; r < 25; ++r) {
+#pragma unroll
+        for (int dx = 0; dx < 5; ++dx) s = fmaf(t[5 * r + dx], *(const float*)(xb + (rows[r] + xs[dx])) - xc, s);
+    }
+    return (double)s + (double)t[kTabSum] * (double)xc;
 }
 
 // One damped Jacobi sweep on a coarse level, xo = xi + omega D^-1 (b - A xi);
@@ -388,7 +401,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_sweep(MgArgs a, MgLevel L, const 
     const double xn = xi[q.n];
     if (a.s->done) return;
     const float* t = tab + (size_t)cls * kTabRow;
-    const double ax = row_dot(L, xi, q.i, q.j, q.k, t);
+    const double ax = row_dot(L, xi, q.i, q.j, q.k, (float)xn, t);
     if (RESID)
         xo[q.n] = (mgv)((bn - ax) * (double)(cls != 0));
     else
@@ -396,50 +409,58 @@ __global__ __launch_bounds__(kBlock) void k_mg_sweep(MgArgs a, MgLevel L, const 
 }
 
 // b_c = P^T r for an even fine width (fnx = 2 C.nx): each lane reads its
-// two fine nodes 2J, 2J+1 of a row as one float2 and takes 2J-1 and 2J+2
-// from the neighbouring lanes (from memory at the ends of the wavefront;
-// across a row boundary the weight is zero). Lanes past the plane work on
-// the last node and store nothing, so every lane takes part in the shuffles.
+// two fine nodes 2J, 2J+1 of a row as one float2 and 2J-1, 2J+2 as single
+// values (clamped at the row ends, where their weight is zero); every load is
+// unconditional, so all 48 are in flight together. Row sums in FP32 (weights
+// 1/4, 3/4, 1), the y and z sums in FP64.
 __global__ __launch_bounds__(kBlock) void k_mg_restrict2(MgArgs a, int fnx, int fny, int fnz, const mgv* __restrict__ r,
                                                           MgLevel C) {
-    const int pl = C.nx * C.ny;
-    int p = (int)blockIdx.x * kBlock + (int)threadIdx.x;
-    const bool valid = p < pl;
-    if (!valid) p = pl - 1;
-    const int Jz = (int)blockIdx.y, Jy = p / C.nx, Jx = p - Jy * C.nx;
-    const int lane = threadIdx.x & 63;
-    double wx[4], wy[4], wz[4];
-    int jy[4];
-    int64_t kz[4];
+    PlaneIdx q;
+    if (!plane_idx(C.nx, C.ny, q)) return;
+    const int Jx = q.i, Jy = q.j, Jz = q.k;
+    float wx[4];
+    double wy[4], wz[4];
+    uint32_t rowo[16];
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
         const int fi = 2 * Jx - 1 + d, fj = 2 * Jy - 1 + d, fk = 2 * Jz - 1 + d;
-        wx[d] = (fi >= 0 && fi < fnx) ? interp_w(fi, Jx, C.nx) : 0.0;
+        wx[d] = (fi >= 0 && fi < fnx) ? (float)interp_w(fi, Jx, C.nx) : 0.0f;
         wy[d] = (fj >= 0 && fj < fny) ? interp_w(fj, Jy, C.ny) : 0.0;
         wz[d] = (fk >= 0 && fk < fnz) ? interp_w(fk, Jz, C.nz) : 0.0;
-        jy[d] = clampi(fj, fny) * fnx;
-        kz[d] = (int64_t)clampi(fk, fnz) * fnx * fny;
     }
-    const bool needL = lane == 0 && Jx > 0, needR = lane == 63 && Jx + 1 < C.nx;
+#pragma unroll
+    for (int dz = 0; dz < 4; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 4; ++dy)
+            rowo[4 * dz + dy] = (uint32_t)clampi(2 * Jz - 1 + dz, fnz) * (uint32_t)(fnx * fny) +
+                                (uint32_t)(clampi(2 * Jy - 1 + dy, fny) * fnx);
+    const uint32_t il = (uint32_t)clampi(2 * Jx - 1, fnx), ip = (uint32_t)(2 * Jx), ir = (uint32_t)clampi(2 * Jx + 2, fnx);
+    float lv[16], rv[16];
+    float2 pv[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        lv[e] = r[rowo[e] + il];
+        pv[e] = *(const float2*)(r + rowo[e] + ip);
+        rv[e] = r[rowo[e] + ir];
+    }
     double s = 0.0;
 #pragma unroll
     for (int dz = 0; dz < 4; ++dz) {
         double sy = 0.0;
 #pragma unroll
         for (int dy = 0; dy < 4; ++dy) {
-            const mgv* row = r + kz[dz] + jy[dy];
-            const float2 pr = *(const float2*)(row + 2 * Jx);
-            float left = __shfl_up(pr.y, 1), right = __shfl_down(pr.x, 1);
-            if (needL) left = row[2 * Jx - 1];
-            if (needR) right = row[2 * Jx + 2];
-            const double sx = wx[0] * (double)left + wx[1] * (double)pr.x + wx[2] * (double)pr.y + wx[3] * (double)right;
-            sy += wy[dy] * sx;
+            const int e = 4 * dz + dy;
+            float sx = wx[0] * lv[e];
+            sx = fmaf(wx[1], pv[e].x, sx);
+            sx = fmaf(wx[2], pv[e].y, sx);
+            sx = fmaf(wx[3], rv[e], sx);
+            sy += wy[dy] * (double)sx;
         }
         s += wz[dz] * sy;
     }
-    const uint8_t u = C.used[(int64_t)Jz * pl + p];
+    const uint8_t u = C.used[q.n];
     if (a.s->done) return;
-    if (valid) C.b[(int64_t)Jz * pl + p] = (mgv)(s * (double)u);
+    C.b[q.n] = (mgv)(s * (double)u);
 }
 
 // b_c = P^T r: coarse node J collects the fine nodes 2J-1 .. 2J+2 of each
@@ -505,6 +526,54 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong(MgArgs a, int fnx, int fn
     const double s1 = py.w0 * (px.w0 * v100 + px.w1 * v101) + py.w1 * (px.w0 * v110 + px.w1 * v111);
     const bool unknown = FINEST ? m == 0 : m != 0;
     xo[q.n] = (mgv)((xv + pz.w0 * s0 + pz.w1 * s1) * (double)unknown);
+}
+
+// The finest-level prolongation for an even width, two x nodes 2m, 2m+1 per
+// lane: both take 3/4 of coarse column m and 1/4 of m - 1 and m + 1
+// respectively (all of m at the grid edges), so a lane reads three coarse
+// values per (y, z) pair of coarse rows and stores a float2. FP32 arithmetic
+// (the weights are exact).
+__global__ __launch_bounds__(kBlock) void k_mg_prolong2(MgArgs a, int fnx, int fny, const uint8_t* __restrict__ type,
+                                                         const mgv* __restrict__ xi, mgv* __restrict__ xo, MgLevel C,
+                                                         const mgv* __restrict__ xc) {
+    const int hx = fnx >> 1;  // lanes per row
+    const int pl = hx * fny;
+    int bx, k;
+    plane_block(bx, k);
+    const int p = bx * kBlock + (int)threadIdx.x;
+    if (p >= pl) return;
+    const int j = p / hx, m = p - j * hx;
+    const int64_t n = (int64_t)k * fnx * fny + (int64_t)j * fnx + 2 * m;
+    const Interp1 py = interp1(j, C.ny), pz = interp1(k, C.nz);
+    const int mw = m > 0 ? m - 1 : m, me = m + 1 < C.nx ? m + 1 : m;
+    const float a0 = m > 0 ? 0.75f : 1.0f, aw = m > 0 ? 0.25f : 0.0f;           // node 2m
+    const float a1 = m + 1 < C.nx ? 0.75f : 1.0f, ae = m + 1 < C.nx ? 0.25f : 0.0f;  // node 2m + 1
+    const int cpl = C.nx * C.ny;
+    const int r00 = pz.c0 * cpl + py.c0 * C.nx, r01 = pz.c0 * cpl + py.c1 * C.nx;
+    const int r10 = pz.c1 * cpl + py.c0 * C.nx, r11 = pz.c1 * cpl + py.c1 * C.nx;
+    const float w00 = (float)(pz.w0 * py.w0), w01 = (float)(pz.w0 * py.w1), w10 = (float)(pz.w1 * py.w0),
+                w11 = (float)(pz.w1 * py.w1);
+    const float c00 = xc[r00 + m], w00v = xc[r00 + mw], e00 = xc[r00 + me];
+    const float c01 = xc[r01 + m], w01v = xc[r01 + mw], e01 = xc[r01 + me];
+    const float c10 = xc[r10 + m], w10v = xc[r10 + mw], e10 = xc[r10 + me];
+    const float c11 = xc[r11 + m], w11v = xc[r11 + mw], e11 = xc[r11 + me];
+    const float2 xv = *(const float2*)(xi + n);
+    const uchar2 tv = *(const uchar2*)(type + n);
+    if (a.s->done) return;
+    // per coarse (y, z) row: the column sums for node 2m (west side) and 2m + 1 (east side)
+    float s0 = 0.0f, s1 = 0.0f;
+    s0 = fmaf(w00, fmaf(a0, c00, aw * w00v), s0);
+    s1 = fmaf(w00, fmaf(a1, c00, ae * e00), s1);
+    s0 = fmaf(w01, fmaf(a0, c01, aw * w01v), s0);
+    s1 = fmaf(w01, fmaf(a1, c01, ae * e01), s1);
+    s0 = fmaf(w10, fmaf(a0, c10, aw * w10v), s0);
+    s1 = fmaf(w10, fmaf(a1, c10, ae * e10), s1);
+    s0 = fmaf(w11, fmaf(a0, c11, aw * w11v), s0);
+    s1 = fmaf(w11, fmaf(a1, c11, ae * e11), s1);
+    float2 out;
+    out.x = (xv.x + s0) * (float)(tv.x == 0);
+    out.y = (xv.y + s1) * (float)(tv.y == 0);
+    *(float2*)(xo + n) = out;
 }
 
 // Coarsest level: x = A^-1 b with the stored inverse, one wavefront per row.
@@ -722,6 +791,9 @@ static void row_classes(const std::vector<float>& rows, int64_t n, double omega,
             float* t = tab.data() + (size_t)cls * kTabRow;
             std::memcpy(t, r, 125 * sizeof(float));
             t[kTabInvD] = (float)(omega / (double)r[kCenter]);
+            double sum = 0.0;
+            for (int o = 0; o < 125; ++o) sum += (double)r[o];
+            t[kTabSum] = (float)sum;
             cands.push_back(cls);
         }
         ids[I] = cls;
@@ -944,8 +1016,12 @@ float* mg_vcycle(pic_ctx* c, const TB* b0, double* part_rr, double* part_bb, dou
     // finest level up: correction, two sweeps (the last with the r.z partials)
     MgLevel& L = h->lv[0];
     int t3 = timed ? tic(c, PIC_T_MG_CORR) : -1;
-    hipLaunchKernelGGL(k_mg_prolong<true>, plane_grid(g.nx, g.ny, g.nz), dim3(kBlock), 0, c->stream, a, g.nx, g.ny, g.nz,
-                       (const uint8_t*)c->buf.node_type, (const mgv*)L.x0, L.x1, h->lv[1], (const mgv*)res[1]);
+    if (g.nx % 2 == 0)
+        hipLaunchKernelGGL(k_mg_prolong2, plane_grid(g.nx / 2, g.ny, g.nz), dim3(kBlock), 0, c->stream, a, g.nx, g.ny,
+                           (const uint8_t*)c->buf.node_type, (const mgv*)L.x0, L.x1, h->lv[1], (const mgv*)res[1]);
+    else
+        hipLaunchKernelGGL(k_mg_prolong<true>, plane_grid(g.nx, g.ny, g.nz), dim3(kBlock), 0, c->stream, a, g.nx, g.ny,
+                           g.nz, (const uint8_t*)c->buf.node_type, (const mgv*)L.x0, L.x1, h->lv[1], (const mgv*)res[1]);
     toc(c, t3);
     hipLaunchKernelGGL((k_mg_fine_sweep<kFinePlain, false, TB>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream, a, b0,
                        (const mgv*)L.x1, L.x0, h->zm_kc);
