@@ -178,8 +178,8 @@ def main():
     ap.add_argument("--skip-zero-solve", action="store_true")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned warm-start leg (training on pairs of this run, then iteration counts)")
-    ap.add_argument("--learned-pairs", type=int, default=8)
-    ap.add_argument("--learned-iters", type=int, default=100)
+    ap.add_argument("--learned-pairs", type=int, default=16)
+    ap.add_argument("--learned-iters", type=int, default=300)
     ap.add_argument("--prof-steps", type=int, default=5,
                     help="steps of the profiled pass after the timed region (per-kernel HIP-event timings)")
     ap.add_argument("--unet", action="store_true",
@@ -414,8 +414,9 @@ def learned_leg(sim, pic, args, log):
     """The learned warm start on this workload: training pairs from the
     running simulation (a tight solve, then pic_training_sample, every two
     steps), Adam on the library's network kernels, then on a later state the
-    iterations to 1e-8 of plain CG and of MG-PCG from a zero guess, from
-    V0 phi1 and from the learned guess."""
+    iterations to 1e-8 of plain CG and of MG-PCG from a zero guess, from the
+    previous step's potential, from V0 phi1 and from the learned guess (the
+    raw network output and its energy-norm projection)."""
     import torch
     from paper_2402_08404_amd import warmstart
     cfg = sim.cfg
@@ -438,12 +439,17 @@ def learned_leg(sim, pic, args, log):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     sim.step(3, pic.STEP_FULL)  # a state the network has not seen
+    # one more step without its solve: phi is then the previous step's
+    # potential (the "previous" guess of the step solve)
+    sim.step(1, pic.STEP_FULL & ~pic.STEP_SOLVE)
     net.sync()
-    pic.pic_set_learned_guess(sim.ctx, net.net, 2)
     res = {}
     for sname, solver in (("plain", pic.PIC_SOLVER_CG), ("mgcg", pic.PIC_SOLVER_MGCG)):
-        for gname, guess in (("zero", pic.PIC_GUESS_ZERO), ("laplace", pic.PIC_GUESS_LAPLACE),
-                             ("learned", pic.PIC_GUESS_LEARNED)):
+        for gname, guess, project in (("zero", pic.PIC_GUESS_ZERO, True), ("previous", pic.PIC_GUESS_PREVIOUS, True),
+                                      ("laplace", pic.PIC_GUESS_LAPLACE, True),
+                                      ("learned_raw", pic.PIC_GUESS_LEARNED, False),
+                                      ("learned", pic.PIC_GUESS_LEARNED, True)):
+            pic.pic_set_learned_guess(sim.ctx, net.net, 2, project)
             saved = sim.phi.clone()
             torch.cuda.synchronize()
             t1 = time.perf_counter()
@@ -454,9 +460,12 @@ def learned_leg(sim, pic, args, log):
     pic.pic_set_learned_guess(sim.ctx, None)
     net.close()
     log(f"[bench] learned leg: {args.learned_pairs} pairs, {args.learned_iters} Adam steps, {t_train:.1f} s")
-    return {"pairs": args.learned_pairs, "adam_steps": args.learned_iters, "loss_first": losses[0],
-            "loss_last": losses[-1], "train_s": t_train, "solves": res,
-            "plain_gain_vs_zero": res["plain_zero"]["iters"] / max(res["plain_learned"]["iters"], 1)}
+    m = min(10, len(losses))
+    return {"pairs": args.learned_pairs, "adam_steps": args.learned_iters,
+            "loss_first10": sum(losses[:m]) / m, "loss_last10": sum(losses[-m:]) / m, "train_s": t_train,
+            "solves": res,
+            "plain_gain_vs_zero": res["plain_zero"]["iters"] / max(res["plain_learned"]["iters"], 1),
+            "plain_gain_vs_laplace": res["plain_laplace"]["iters"] / max(res["plain_learned"]["iters"], 1)}
 
 
 def batch_main(args, log):

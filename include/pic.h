@@ -314,8 +314,14 @@ void unet_destroy(unet* net);
 /* Use net (created with batch 1 over nz x ny x nx on the context's stream)
  * for PIC_GUESS_LEARNED; NULL detaches. The network must outlive its use.
  * smooth_passes (0..64) binomial [1 2 1]/4 filters along x, y and z are
- * applied to the network output before it enters the guess. */
-pic_status pic_set_learned_guess(pic_ctx* ctx, unet* net, int32_t smooth_passes);
+ * applied to the network output y before it enters the guess
+ * V0 phi1 + gamma y (free nodes). project = 0: gamma = e s / (eps0 h), the
+ * network's own scale; project = 1: gamma = (y.q) / (y.L y), q the charge
+ * term and L the operator of Eq. poi, the weight that minimizes the energy
+ * norm of the error along y (the guess is then never worse in that norm than
+ * V0 phi1; one extra pass over the grid). Invalid arguments:
+ * PIC_E_INVALID_ARG. */
+pic_status pic_set_learned_guess(pic_ctx* ctx, unet* net, int32_t smooth_passes, int32_t project);
 /* A training pair from the current state: x = q / s from rho and
  * y = (phi - V0 phi1) eps0 h / (e s) from phi (solve to a tight tolerance
  * first). x, y: device fp32 [nz][ny][nx]; scale (optional, host) receives s

@@ -50,8 +50,10 @@ struct DevState {
     unsigned int red_count;
     // mixed-precision refinement
     double rr_outer;
-    // learned warm start: s = max |q| of the current charge
+    // learned warm start: s = max |q| of the current charge; gamma = the
+    // weight of the network output y in the guess V0 phi1 + gamma y
     double learn_scale;
+    double learn_gamma;
 };
 
 // Cells are numbered tile-major: tiles of kTile^3 cells, tile index
@@ -354,6 +356,7 @@ struct pic_ctx {
     hipGraphExec_t pcg_exec = nullptr, mix_exec = nullptr;
     int last_iters[3] = {0, 0, 0};   // iterations of the last solve per solver (first launch chunk)
     int learn_smooth = 0;            // binomial filter passes on its output
+    int learn_project = 1;           // weight the network output by the energy-norm projection
     double* phi_prev = nullptr;      // potential of the previous step solve (extrapolated guess)
     int phi_hist = 0;                // consecutive step solves whose potential phi_prev / phi hold
     // host state

@@ -1224,14 +1224,69 @@ __global__ void k_learn_smooth(const float* __restrict__ yi, float* __restrict__
 }
 
 // phi = V0 phi1 + (e s / (eps0 h)) y on free nodes, V0 phi1 on fixed nodes
+// phi = V0 phi1 + gamma y on free nodes (gamma from st), V0 phi1 elsewhere
+// and without a network output
 __global__ void k_learn_phi(const double* __restrict__ phi1, const float* __restrict__ y, const uint8_t* __restrict__ type,
-                            int64_t n, double V0, double c0, const DevState* st, double* __restrict__ phi) {
-    double s = st->learn_scale;
+                            int64_t n, double V0, const DevState* st, double* __restrict__ phi) {
+    const double gam = st->learn_gamma;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double v = V0 * phi1[i];
-        if (y && type[i] == 0 && s > 0.0) v += c0 * s * (double)y[i];
+        if (y && type[i] == 0) v += gam * (double)y[i];
         phi[i] = v;
     }
+}
+
+// Partials of y.q and y.(L y) over the free nodes, with y taken as zero on
+// fixed nodes, L the finite-volume operator of Eq. poi and q = rho qscale its
+// charge term. V0 phi1 satisfies the charge-free problem, so the residual of
+// V0 phi1 + g y is q - g L y and g* = (y.q) / (y.L y) minimizes the energy
+// norm of the error along y: the guess is never worse in that norm than V0
+// phi1 alone.
+__device__ inline double learn_half(int i, int n) { return (i == 0 || i == n - 1) ? 0.5 : 1.0; }
+
+__global__ __launch_bounds__(kBlock) void k_learn_proj(Grid g, const float* __restrict__ y, const int64_t* __restrict__ rho,
+                                                        const uint8_t* __restrict__ type, double qscale,
+                                                        double* __restrict__ part) {
+    const int64_t pl = (int64_t)g.nx * g.ny;
+    double yq = 0.0, yly = 0.0;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < g.nn; n += (int64_t)gridDim.x * blockDim.x) {
+        if (type[n] != 0) continue;
+        const int i = (int)(n % g.nx), j = (int)((n / g.nx) % g.ny), k = (int)(n / pl);
+        const double fx = learn_half(j, g.ny) * learn_half(k, g.nz), fy = learn_half(i, g.nx) * learn_half(k, g.nz),
+                     fz = learn_half(i, g.nx) * learn_half(j, g.ny);
+        const double yn = y[n];
+        const int64_t nb[6] = {n - 1, n + 1, n - g.nx, n + g.nx, n - pl, n + pl};
+        const bool has[6] = {i > 0, i < g.nx - 1, j > 0, j < g.ny - 1, k > 0, k < g.nz - 1};
+        const double f[6] = {fx, fx, fy, fy, fz, fz};
+        double ly = 0.0;
+        for (int d = 0; d < 6; ++d) {
+            if (!has[d]) continue;
+            const double ym = type[nb[d]] == 0 ? (double)y[nb[d]] : 0.0;
+            ly += f[d] * (yn - ym);
+        }
+        yq += yn * ((double)rho[n] * qscale);
+        yly += yn * ly;
+    }
+    __shared__ double sh[kBlock / 64];
+    const double a = block_sum(yq, sh);
+    __syncthreads();
+    const double b = block_sum(yly, sh);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = a;
+        part[2 * blockIdx.x + 1] = b;
+    }
+}
+
+// gamma: the projection weight (project != 0), else the network's own
+// scaling e s / (eps0 h)
+__global__ void k_learn_gamma(const double* __restrict__ part, int nparts, int project, double c0, DevState* st) {
+    if (threadIdx.x != 0) return;
+    double a = 0.0, b = 0.0;
+    for (int i = 0; i < nparts; ++i) {
+        a += part[2 * i];
+        b += part[2 * i + 1];
+    }
+    st->learn_gamma = project ? (b > 0.0 ? a / b : 0.0) : (st->learn_scale > 0.0 ? c0 * st->learn_scale : 0.0);
 }
 
 // y = (phi - V0 phi1) eps0 h / (e s) on free nodes, zero elsewhere
@@ -1272,9 +1327,17 @@ int guess_phi(pic_ctx* c, bool with_net) {
         }
         y = a;
     }
-    double c0 = kQe / (kEps0 * c->cfg.h);
+    if (y) {
+        const unsigned G = 256;
+        double* part = c->partials;  // idle between solves
+        const double qscale = ldexp(1.0, -40) * kQe / (kEps0 * c->cfg.h);
+        hipLaunchKernelGGL(k_learn_proj, dim3(G), dim3(kBlock), 0, c->stream, c->g, y, (const int64_t*)c->buf.rho,
+                           (const uint8_t*)c->buf.node_type, qscale, part);
+        hipLaunchKernelGGL(k_learn_gamma, dim3(1), dim3(64), 0, c->stream, (const double*)part, (int)G,
+                           c->learn_project, kQe / (kEps0 * c->cfg.h), c->st);
+    }
     hipLaunchKernelGGL(k_learn_phi, dim3(4096), dim3(kBlock), 0, c->stream, (const double*)c->buf.phi1, y,
-                       (const uint8_t*)c->buf.node_type, n, c->V0, c0, (const pic::DevState*)c->st,
+                       (const uint8_t*)c->buf.node_type, n, c->V0, (const pic::DevState*)c->st,
                        (double*)c->buf.phi);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
@@ -1283,12 +1346,13 @@ int guess_phi(pic_ctx* c, bool with_net) {
 
 extern "C" {
 
-pic_status pic_set_learned_guess(pic_ctx* c, unet* u, int32_t smooth_passes) {
-    if (!c || smooth_passes < 0 || smooth_passes > 64) return PIC_E_INVALID_ARG;
+pic_status pic_set_learned_guess(pic_ctx* c, unet* u, int32_t smooth_passes, int32_t project) {
+    if (!c || smooth_passes < 0 || smooth_passes > 64 || project < 0 || project > 1) return PIC_E_INVALID_ARG;
     if (u && (u->B != 1 || u->D != c->cfg.nz || u->H != c->cfg.ny || u->W != c->cfg.nx || u->stream != c->stream))
         return PIC_E_INVALID_ARG;
     c->learned = u;
     c->learn_smooth = smooth_passes;
+    c->learn_project = project;
     return PIC_OK;
 }
 

@@ -121,7 +121,7 @@ def lib():
         L.unet_sync_params.argtypes = [vp]
         L.unet_destroy.argtypes = [vp]
         L.unet_destroy.restype = None
-        L.pic_set_learned_guess.argtypes = [vp, vp, C.c_int32]
+        L.pic_set_learned_guess.argtypes = [vp, vp, C.c_int32, C.c_int32]
         L.pic_training_sample.argtypes = [vp, vp, vp, C.POINTER(C.c_double)]
         for f in ("pic_scratch_size", "pic_init", "pic_inject", "pic_step", "pic_solve_poisson", "pic_moments",
                   "pic_events", "unet_param_count", "unet_workspace_size", "unet_create", "unet_forward",
@@ -264,8 +264,11 @@ def unet_destroy(net):
     lib().unet_destroy(net)
 
 
-def pic_set_learned_guess(ctx, net, smooth_passes: int = 0):
-    _check(lib().pic_set_learned_guess(ctx, net, smooth_passes), ctx)
+def pic_set_learned_guess(ctx, net, smooth_passes: int = 0, project: bool = True):
+    """Attach a network for PIC_GUESS_LEARNED (None detaches); with project
+    the network output is weighted by the energy-norm projection (see
+    include/pic.h)."""
+    _check(lib().pic_set_learned_guess(ctx, net, smooth_passes, 1 if project else 0), ctx)
 
 
 def pic_training_sample(ctx, x: int, y: int) -> float:

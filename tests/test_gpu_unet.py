@@ -149,11 +149,13 @@ def test_training_reduces_loss():
 
 def test_learned_guess_solve():
     """Train on pairs of the small 32 x 32 x 64 workload at several apex
-    fields, then solve a held-out state from the learned guess. The guess
-    must carry most of the charge response (its error against the converged
-    potential well below that of the charge-free guess V0 phi1), and the
-    solve from it must end at the plain solve's result. Iteration counts of
-    both solvers from every guess are printed; the gain in iterations is a
+    fields, then solve a held-out state from the learned guess. The raw
+    network guess must carry most of the charge response (its error against
+    the converged potential well below that of the charge-free guess V0
+    phi1); with the energy-norm projection the guess error, measured with the
+    oracle's operator, must not exceed that of V0 phi1 or of the raw guess;
+    the solve from it must end at the plain solve's result. Iteration counts
+    of both solvers from every guess are printed; the gain in iterations is a
     measurement, not asserted."""
     import dataclasses
     from paper_2402_08404_amd import pic, warmstart
@@ -173,23 +175,40 @@ def test_learned_guess_solve():
     sim.load(W.initial_load(cfg, counts=(20000, 200, 2000), seed=321))
     sim.step(1, pic.STEP_DEPOSIT)
     sim.step(20, pic.STEP_FULL)
-    pic.pic_set_learned_guess(sim.ctx, guess_net.net)
+    pic.pic_set_learned_guess(sim.ctx, guess_net.net, 0, False)
     sim.solve(solver=pic.PIC_SOLVER_CG, guess=pic.PIC_GUESS_ZERO, rtol=1e-12, maxit=100000)
     exact = sim.grid("phi").copy()
     guesses = {}
-    for name, g in (("laplace", pic.PIC_GUESS_LAPLACE), ("learned", pic.PIC_GUESS_LEARNED)):
+    for name, g, proj in (("laplace", pic.PIC_GUESS_LAPLACE, False), ("learned_raw", pic.PIC_GUESS_LEARNED, False),
+                          ("learned", pic.PIC_GUESS_LEARNED, True)):
+        pic.pic_set_learned_guess(sim.ctx, guess_net.net, 0, proj)
         sim.solve(solver=pic.PIC_SOLVER_CG, guess=g, rtol=1e-12, maxit=0, allow_unconverged=True)
         guesses[name] = sim.grid("phi").copy()
     resp = np.linalg.norm(exact - guesses["laplace"])
-    err = np.linalg.norm(guesses["learned"] - exact) / resp
+    err = np.linalg.norm(guesses["learned_raw"] - exact) / resp
     print("relative error of the learned charge response", err, flush=True)
     assert err < 0.25
+    # energy norm of the error from the oracle's operator: the projected
+    # weight can only lower it below that of V0 phi1
+    from oracle import Oracle
+    o = Oracle(cfg, laplace=False)
+    free = (o.type == 0)
+
+    def energy(phi):
+        e = (phi.ravel() - exact.ravel()) * free
+        return float(e @ o.apply_A(e))
+
+    en = {k: energy(v) for k, v in guesses.items()}
+    print("energy norm^2 of the guess errors", en, flush=True)
+    assert en["learned"] <= en["laplace"] * (1 + 1e-9)
+    assert en["learned"] <= en["learned_raw"] * (1 + 1e-9)
     res = {}
     for solver in (pic.PIC_SOLVER_CG, pic.PIC_SOLVER_MGCG):
-        for name, g, sm in (("zero", pic.PIC_GUESS_ZERO, 0), ("laplace", pic.PIC_GUESS_LAPLACE, 0),
-                            ("learned", pic.PIC_GUESS_LEARNED, 0), ("learned+1", pic.PIC_GUESS_LEARNED, 1),
-                            ("learned+2", pic.PIC_GUESS_LEARNED, 2), ("learned+4", pic.PIC_GUESS_LEARNED, 4)):
-            pic.pic_set_learned_guess(sim.ctx, guess_net.net, sm)
+        for name, g, sm, proj in (("zero", pic.PIC_GUESS_ZERO, 0, True), ("laplace", pic.PIC_GUESS_LAPLACE, 0, True),
+                                  ("learned_raw", pic.PIC_GUESS_LEARNED, 0, False),
+                                  ("learned", pic.PIC_GUESS_LEARNED, 0, True),
+                                  ("learned+2", pic.PIC_GUESS_LEARNED, 2, True)):
+            pic.pic_set_learned_guess(sim.ctx, guess_net.net, sm, proj)
             r = sim.solve(solver=solver, guess=g, rtol=1e-8, maxit=100000)
             res[(solver, name)] = (r["iterations"], round(r["relres0"], 4))
             phi = sim.grid("phi")
