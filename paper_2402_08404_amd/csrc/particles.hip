@@ -897,12 +897,12 @@ static unsigned grid_push(int64_t n) {
     return (unsigned)g;
 }
 
-// Cell bins (radix sort of the keys), then the deposit.
+// Cell bins (counting sort of the keys), then the deposit.
 template <typename T>
 static hipError_t bin_t(pic_ctx* c) {
     const Grid& g = c->g;
     int tb = tic(c, PIC_T_BIN);
-    hipError_t e = radix_bins(c);
+    hipError_t e = cell_bins(c);
     toc(c, tb);
     if (e != hipSuccess) return e;
     DepositArgs<T> d;

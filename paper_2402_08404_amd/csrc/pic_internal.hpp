@@ -319,9 +319,7 @@ struct pic_ctx {
     uint32_t* off = nullptr;      // nkeys + 1
     uint32_t* key[3] = {};
     uint32_t* bins = nullptr;     // sum cap
-    uint32_t* rs_keys[2] = {};    // radix sort ping-pong keys (sum cap)
-    uint32_t* rs_vals[2] = {};    // radix sort ping-pong values (sum cap)
-    uint32_t* rs_hist = nullptr;  // digit histograms
+    uint32_t* cursor = nullptr;   // per-key scatter cursors of the cell bins (nkeys + 1)
     uint32_t* big = nullptr;      // big-cell list (nkeys)
     uint32_t* fi_list = nullptr;  // cap neutral
     uint32_t* push_part = nullptr;  // per-block partials of the push kernels (8192 x 8)
@@ -404,7 +402,7 @@ hipError_t scan_u32(pic_ctx* c, const uint32_t* in, uint32_t* out, int64_t n_max
                     uint32_t* total, bool zero_in, bool popcount);
 hipError_t particles_phase(pic_ctx* c, bool move);
 hipError_t collide_phase(pic_ctx* c, bool record);
-hipError_t radix_bins(pic_ctx* c);
+hipError_t cell_bins(pic_ctx* c);
 hipError_t inject_phase(pic_ctx* c);
 hipError_t load_particles(pic_ctx* c, const pic_particles* src);
 hipError_t moments_phase(pic_ctx* c, double* out_dev);
