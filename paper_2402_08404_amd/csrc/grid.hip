@@ -271,41 +271,59 @@ __global__ void k_cg_init(CgArgs a, int zero_guess) {
 }
 
 // r = q/(eps0 h) - L(phi) with the Dirichlet values in phi, partials of r.r
-// and of b.b with b = q/(eps0 h) + Dirichlet lifts; p_old cleared.
-__global__ __launch_bounds__(kBlock) void k_cg_resid(CgArgs a) {
+// and of b.b with b = q/(eps0 h) + Dirichlet lifts; p_old cleared. Blocks of
+// kResidBlock threads over the same kCgBlocks chunks as the CG kernels (so
+// the partial counts match); neighbour loads are unconditional (read at the
+// node itself with weight zero at the grid faces), so a node's loads are in
+// flight together.
+constexpr int kResidBlock = 1024;
+
+__global__ __launch_bounds__(kResidBlock) void k_cg_resid(CgArgs a) {
     const Grid& g = a.g;
     int64_t b0 = xcd_block(blockIdx.x, gridDim.x) * a.chunk;
     int64_t b1 = b0 + a.chunk < g.nn ? b0 + a.chunk : g.nn;
-    int64_t pl = (int64_t)g.nx * g.ny;
+    const int64_t pl = (int64_t)g.nx * g.ny;
     double bb = 0.0, rr = 0.0;
     NodeWalk wk(b0 + threadIdx.x, blockDim.x, g.nx, g.ny);
     for (int64_t n = b0 + threadIdx.x; n < b1; n += blockDim.x, wk.advance()) {
         ((double*)a.p_old)[n] = 0.0;
-        if (a.type[n] != 0) continue;
-        int i = wk.i, j = wk.j, k = wk.k;
-        double fx = half_at_edge(j, g.ny) * half_at_edge(k, g.nz);
-        double fy = half_at_edge(i, g.nx) * half_at_edge(k, g.nz);
-        double fz = half_at_edge(i, g.nx) * half_at_edge(j, g.ny);
-        double xi = a.x[n];
-        double qv = (double)a.rho[n] * a.qscale;
-        double bv = qv, lx = 0.0;
-        int64_t nb[6] = {n - 1, n + 1, n - g.nx, n + g.nx, n - pl, n + pl};
-        bool has[6] = {i > 0, i < g.nx - 1, j > 0, j < g.ny - 1, true, true};
-        double f[6] = {fx, fx, fy, fy, fz, fz};
+        const int i = wk.i, j = wk.j, k = wk.k;
+        const double fx = half_at_edge(j, g.ny) * half_at_edge(k, g.nz);
+        const double fy = half_at_edge(i, g.nx) * half_at_edge(k, g.nz);
+        const double fz = half_at_edge(i, g.nx) * half_at_edge(j, g.ny);
+        const bool hs[6] = {i > 0, i < g.nx - 1, j > 0, j < g.ny - 1, k > 0, k < g.nz - 1};
+        const int64_t d[6] = {-1, 1, -(int64_t)g.nx, (int64_t)g.nx, -pl, pl};
+        const double f[6] = {fx, fx, fy, fy, fz, fz};
+        const double xi = a.x[n];
+        const bool fr = a.type[n] == 0;
+        const double qv = (double)a.rho[n] * a.qscale;
+        double xj[6];
+        uint8_t tj[6];
 #pragma unroll
-        for (int d = 0; d < 6; ++d) {
-            if (!has[d]) continue;
-            double xj = a.x[nb[d]];
-            lx += f[d] * (xi - xj);
-            if (a.type[nb[d]] != 0) bv += f[d] * xj;
+        for (int q = 0; q < 6; ++q) {
+            const int64_t m = hs[q] ? n + d[q] : n;
+            xj[q] = a.x[m];
+            tj[q] = a.type[m];
         }
-        double rv = qv - lx;
-        a.r[n] = rv;
-        bb += bv * bv;
-        rr += rv * rv;
+        double lx = 0.0, bv = qv;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const double w = hs[q] ? f[q] : 0.0;
+            lx += w * (xi - xj[q]);
+            bv += (tj[q] != 0 ? w : 0.0) * xj[q];
+        }
+        const double rv = qv - lx;
+        if (fr) {
+            a.r[n] = rv;
+            bb += bv * bv;
+            rr += rv * rv;
+        }
     }
-    write_partial(bb, a.part_bb);
-    write_partial(rr, a.part_rr);
+    __shared__ double sh[kResidBlock / 64];
+    const double tb = block_sum(bb, sh);
+    if (threadIdx.x == 0) a.part_bb[blockIdx.x] = tb;
+    const double tr = block_sum(rr, sh);
+    if (threadIdx.x == 0) a.part_rr[blockIdx.x] = tr;
 }
 
 // Iteration it: finish r.r of the previous iteration (or of the initial
@@ -431,7 +449,7 @@ int cg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess, 
     a.chunk = ((g.nn + kCgBlocks - 1) / kCgBlocks + kBlock - 1) / kBlock * kBlock;
     hipLaunchKernelGGL(k_cg_setup, dim3(1), dim3(1), 0, c->stream, c->st, rtol, maxit);
     hipLaunchKernelGGL(k_cg_init, dim3((unsigned)G), dim3(kBlock), 0, c->stream, a, guess == PIC_GUESS_ZERO);
-    hipLaunchKernelGGL(k_cg_resid, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(k_cg_resid, dim3(kCgBlocks), dim3(kResidBlock), 0, c->stream, a);
     double* pa = c->cg_p0;
     double* pb = c->cg_p1;
     int chunk = 8;
@@ -793,7 +811,7 @@ int mgcg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess
     a.chunk = ((g.nn + kCgBlocks - 1) / kCgBlocks + kBlock - 1) / kBlock * kBlock;
     hipLaunchKernelGGL(k_cg_setup, dim3(1), dim3(1), 0, c->stream, c->st, rtol, maxit);
     hipLaunchKernelGGL(k_cg_init, dim3((unsigned)G), dim3(kBlock), 0, c->stream, a, guess == PIC_GUESS_ZERO);
-    hipLaunchKernelGGL(k_cg_resid, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(k_cg_resid, dim3(kCgBlocks), dim3(kResidBlock), 0, c->stream, a);
     int e = pcg_iterate<double>(c, phi, c->cg_r, c->cg_p0, c->cg_p1, c->cg_q, maxit, 0);
     if (e) return e;
     hipLaunchKernelGGL(k_cg_zero_free, dim3((unsigned)G), dim3(kBlock), 0, c->stream, g, c->buf.node_type, phi,
@@ -890,7 +908,7 @@ int mixed_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int gues
     double bn = 0.0, rn = 0.0, rn0 = -1.0;
     bool conv = false;
     for (int outer = 0; outer < 40; ++outer) {
-        hipLaunchKernelGGL(k_cg_resid, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a);
+        hipLaunchKernelGGL(k_cg_resid, dim3(kCgBlocks), dim3(kResidBlock), 0, c->stream, a);
         hipLaunchKernelGGL(k_mix_test, dim3(1), dim3(kBlock), 0, c->stream, (const double*)a.part_rr,
                            (const double*)a.part_bb, c->st);
         (void)hipMemcpyAsync(c->host_st, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream);

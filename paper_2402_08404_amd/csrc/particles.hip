@@ -450,17 +450,23 @@ __device__ inline double pnull_of(const MccArgs<T>& a, int cls, int NT) {
 // Pairs of one class inside one cell, sequentially. Entries are sorted by
 // (species, id); [a0, a0+na) charged species, [b0, b0+nb) neutrals.
 // used: bit r set if the neutral of rank r had an event (input and output).
+// pn: P_null of this class by target count (NT <= kSmallCell), or null to
+// compute it.
 template <typename T>
 __device__ void cell_class_seq(const MccArgs<T>& a, int cls, uint32_t cell, const uint64_t* kk, const uint32_t* ee,
-                               int a0, int na, int b0, int nb, uint32_t& used, int cnt[5]) {
+                               int a0, int na, int b0, int nb, uint32_t& used, int cnt[5], const double* pn = nullptr) {
     if (na == 0 || nb == 0) return;
     bool a_proj = na <= nb;
     int P0 = a_proj ? a0 : b0, NP = a_proj ? na : nb;
     int T0 = a_proj ? b0 : a0, NT = a_proj ? nb : na;
-    Draw2 dc = draw2(a.seed, linear_cell(a.g, cell), a.step, cls == 1 ? kTagPair1 : kTagPair2, 0);
-    int shift = (int)floor(dc.a * (double)NT);
-    shift = shift > NT - 1 ? NT - 1 : shift;
-    double pnull = pnull_of(a, cls, NT);
+    // the pairing shift (a single target needs no draw: the shift is 0)
+    int shift = 0;
+    if (NT > 1) {
+        Draw2 dc = draw2(a.seed, linear_cell(a.g, cell), a.step, cls == 1 ? kTagPair1 : kTagPair2, 0);
+        shift = (int)floor(dc.a * (double)NT);
+        shift = shift > NT - 1 ? NT - 1 : shift;
+    }
+    double pnull = pn ? pn[NT] : pnull_of(a, cls, NT);
     for (int i = 0; i < NP; ++i) {
         int pi = P0 + i, ti = T0 + (shift + i) % NT;
         int ai = a_proj ? pi : ti, bi = a_proj ? ti : pi;
@@ -492,6 +498,13 @@ __device__ inline void flush_counts(DevState* st, int cnt[5]) {
 // queued for the wavefront kernel.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_mcc_small(MccArgs<T> a) {
+    // P_null by class and target count, once per block
+    __shared__ double pn[2][kSmallCell + 1];
+    if (threadIdx.x < 2 * (kSmallCell + 1)) {
+        const int cls = 1 + (int)threadIdx.x / (kSmallCell + 1), nt = (int)threadIdx.x % (kSmallCell + 1);
+        pn[cls - 1][nt] = nt > 0 ? pnull_of(a, cls, nt) : 0.0;
+    }
+    __syncthreads();
     int cnt[5] = {0, 0, 0, 0, 0};
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.nc; c += stride) {
@@ -529,8 +542,8 @@ __global__ __launch_bounds__(kBlock) void k_mcc_small(MccArgs<T> a) {
         }
         int nn = n - ne - ni;
         uint32_t used = 0;
-        cell_class_seq(a, 1, (uint32_t)c, kk, ee, 0, ne, ne + ni, nn, used, cnt);
-        cell_class_seq(a, 2, (uint32_t)c, kk, ee, ne, ni, ne + ni, nn, used, cnt);
+        cell_class_seq(a, 1, (uint32_t)c, kk, ee, 0, ne, ne + ni, nn, used, cnt, pn[0]);
+        cell_class_seq(a, 2, (uint32_t)c, kk, ee, ne, ni, ne + ni, nn, used, cnt, pn[1]);
     }
     flush_counts<T>(a.st, cnt);
 }
