@@ -494,56 +494,97 @@ __device__ inline void flush_counts(DevState* st, int cnt[5]) {
     }
 }
 
-// One thread per cell with at most kSmallCell particles; larger cells are
-// queued for the wavefront kernel.
+// Collisions of one cell of 2 .. kSmallCell particles (one lane).
+template <typename T>
+__device__ inline void mcc_cell(const MccArgs<T>& a, uint32_t c, uint32_t o0, int n, const double (*pn)[kSmallCell + 1],
+                                int cnt[5]) {
+    uint64_t kk[kSmallCell];
+    uint32_t ee[kSmallCell];
+    for (int t = 0; t < n; ++t) {
+        uint32_t e = a.bins[o0 + t];
+        uint32_t s = e >> 30;
+        uint32_t id = a.sp[s].id[e & 0x3FFFFFFFu];
+        uint64_t k = ((uint64_t)s << 32) | id;
+        int u = t;
+        while (u > 0 && kk[u - 1] > k) {
+            kk[u] = kk[u - 1];
+            ee[u] = ee[u - 1];
+            --u;
+        }
+        kk[u] = k;
+        ee[u] = e;
+    }
+    if (a.write_sorted)
+        for (int t = 0; t < n; ++t) a.bins[o0 + t] = ee[t];
+    int ne = 0, ni = 0;
+    for (int t = 0; t < n; ++t) {
+        uint32_t s = (uint32_t)(kk[t] >> 32);
+        ne += s == 0;
+        ni += s == 1;
+    }
+    int nn = n - ne - ni;
+    uint32_t used = 0;
+    cell_class_seq(a, 1, c, kk, ee, 0, ne, ne + ni, nn, used, cnt, pn[0]);
+    cell_class_seq(a, 2, c, kk, ee, ne, ni, ne + ni, nn, used, cnt, pn[1]);
+}
+
+// Cells with 2 .. kSmallCell particles, one lane each; larger cells are
+// queued for the wavefront kernel. Most cells hold fewer than two particles,
+// so each wavefront scans its own range of cells 64 at a time and gathers
+// the cells with work in a queue in LDS (ballot and prefix count), then runs
+// 64 of them at once with every lane busy.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_mcc_small(MccArgs<T> a) {
     // P_null by class and target count, once per block
     __shared__ double pn[2][kSmallCell + 1];
+    __shared__ uint32_t queue[kBlock / 64][128];
     if (threadIdx.x < 2 * (kSmallCell + 1)) {
         const int cls = 1 + (int)threadIdx.x / (kSmallCell + 1), nt = (int)threadIdx.x % (kSmallCell + 1);
         pn[cls - 1][nt] = nt > 0 ? pnull_of(a, cls, nt) : 0.0;
     }
     __syncthreads();
     int cnt[5] = {0, 0, 0, 0, 0};
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.nc; c += stride) {
-        uint32_t o0 = a.off[c];
-        int n = (int)(a.off[c + 1] - o0);
-        if (n < 2) continue;
-        if (n > kSmallCell) {
-            unsigned long long p = atomicAdd(&a.st->n_big, 1ull);
-            a.big[p] = (uint32_t)c;
-            continue;
-        }
-        uint64_t kk[kSmallCell];
-        uint32_t ee[kSmallCell];
-        for (int t = 0; t < n; ++t) {
-            uint32_t e = a.bins[o0 + t];
-            uint32_t s = e >> 30;
-            uint32_t id = a.sp[s].id[e & 0x3FFFFFFFu];
-            uint64_t k = ((uint64_t)s << 32) | id;
-            int u = t;
-            while (u > 0 && kk[u - 1] > k) {
-                kk[u] = kk[u - 1];
-                ee[u] = ee[u - 1];
-                --u;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t* q = queue[w];
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+    const int64_t gw = (int64_t)blockIdx.x * (kBlock / 64) + w;
+    const int64_t per = ((a.nc + nw - 1) / nw + 63) / 64 * 64;
+    const int64_t cb = gw * per, ce = cb + per < a.nc ? cb + per : a.nc;
+    int qn = 0;  // the same in every lane
+    int64_t c0 = cb;
+    while (c0 < ce || qn > 0) {
+        while (qn < 64 && c0 < ce) {
+            const int64_t c = c0 + lane;
+            int n = 0;
+            uint32_t o0 = 0;
+            if (c < ce) {
+                o0 = a.off[c];
+                n = (int)(a.off[c + 1] - o0);
             }
-            kk[u] = k;
-            ee[u] = e;
+            if (n > kSmallCell) {
+                unsigned long long p = atomicAdd(&a.st->n_big, 1ull);
+                a.big[p] = (uint32_t)c;
+            }
+            const bool act = n >= 2 && n <= kSmallCell;
+            const unsigned long long m = __ballot(act);
+            if (act) q[qn + __popcll(m & ((1ull << lane) - 1ull))] = (uint32_t)c;
+            qn += __popcll(m);
+            c0 += 64;
         }
-        if (a.write_sorted)
-            for (int t = 0; t < n; ++t) a.bins[o0 + t] = ee[t];
-        int ne = 0, ni = 0;
-        for (int t = 0; t < n; ++t) {
-            uint32_t s = (uint32_t)(kk[t] >> 32);
-            ne += s == 0;
-            ni += s == 1;
+        __builtin_amdgcn_wave_barrier();
+        const int take = qn < 64 ? qn : 64;
+        if (lane < take) {
+            const uint32_t c = q[lane];
+            const uint32_t o0 = a.off[c];
+            mcc_cell(a, c, o0, (int)(a.off[c + 1] - o0), pn, cnt);
         }
-        int nn = n - ne - ni;
-        uint32_t used = 0;
-        cell_class_seq(a, 1, (uint32_t)c, kk, ee, 0, ne, ne + ni, nn, used, cnt, pn[0]);
-        cell_class_seq(a, 2, (uint32_t)c, kk, ee, ne, ni, ne + ni, nn, used, cnt, pn[1]);
+        // move the cells not taken to the front of the queue
+        const int rest = qn - take;
+        const uint32_t keep = lane < rest ? q[take + lane] : 0u;
+        __builtin_amdgcn_wave_barrier();
+        if (lane < rest) q[lane] = keep;
+        __builtin_amdgcn_wave_barrier();
+        qn = rest;
     }
     flush_counts<T>(a.st, cnt);
 }
