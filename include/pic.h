@@ -110,7 +110,7 @@ typedef struct pic_config {
     int32_t step_maxit;    /* iteration limit of the solve inside pic_step */
     int32_t sort_every;    /* reorder particles by cell every this many collide phases (0: never) */
     int64_t id_capacity;   /* largest particle id + 1 the run may reach (0: 8 x total capacity) */
-    int32_t stencil_blocks; /* about this many blocks per z-marching solver kernel (0: 1024; 64..2048) */
+    int32_t stencil_blocks; /* about this many blocks per z-marching solver kernel (0: 1024; 64..4096) */
     int32_t step_guess;    /* guess of the solve inside pic_step: 0 the previous potential, 1 linear
                               extrapolation 2 phi_n - phi_{n-1} from the two previous step solves */
 } pic_config;

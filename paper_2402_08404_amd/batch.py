@@ -106,7 +106,7 @@ def shape_key(cfg) -> str:
     return f"{cfg.nx}x{cfg.ny}x{cfg.nz}"
 
 
-def autotune(items, candidates_sort=(8, 16, 32), candidates_blocks=(512, 1024, 2048), steps: int = 3,
+def autotune(items, candidates_sort=(8, 16, 32), candidates_blocks=(1024, 2048, 4096), steps: int = 3,
              warmup: int = 2, log=None) -> dict:
     """For each grid shape of the sweep, time `steps` full steps of its
     smallest instance for each candidate setting (one parameter at a time,

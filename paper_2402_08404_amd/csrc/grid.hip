@@ -655,6 +655,7 @@ static unsigned pair_grid(int nx, int ny, int nz, int target, int* kc) {
     int64_t cols = (int64_t)((nx + 127) / 128) * ((ny + 3) / 4);
     int64_t k = (nz * cols + target - 1) / target;
     if (k < 1) k = 1;
+    while (k < nz && cols * ((nz + k - 1) / k) > kMaxStencilBlocks) ++k;  // partial-sum slots
     *kc = (int)k;
     return (unsigned)(cols * ((nz + k - 1) / k));
 }
@@ -717,7 +718,7 @@ static int pcg_iterate(pic_ctx* c, TP* x, TP* r, TP* p0, TP* p1, TP* q, int maxi
     const bool pair = sizeof(TP) == 8 && (g.nx % 2) == 0;
     unsigned zb = pair ? pair_grid(g.nx, g.ny, g.nz, stencil_target(c), &kc)
                        : zmarch_grid(g.nx, g.ny, g.nz, stencil_target(c), 1, &kc);
-    if (zb > 4096) return -3;
+    if (zb > kMaxStencilBlocks) return -3;
     // one iteration: V-cycle, p update and A p, x and r update
     auto iteration = [&](TP* p_old, TP* p_new, bool timed) {
         int tm = timed ? tic(c, PIC_T_MG) : -1;

@@ -854,7 +854,7 @@ int mg_setup(pic_ctx* c) {
     h->post = 2;
     h->zm_blocks = zmarch_grid(c->g.nx, c->g.ny, c->g.nz, stencil_target(c), 1, &h->zm_kc);
     // plane grids: nz in gridDim.y, the plane size in 32-bit indices
-    if (h->zm_blocks > 4096 || c->g.nz > 65535 || (int64_t)c->g.nx * c->g.ny >= ((int64_t)1 << 30)) {
+    if (h->zm_blocks > kMaxStencilBlocks || c->g.nz > 65535 || (int64_t)c->g.nx * c->g.ny >= ((int64_t)1 << 30)) {
         delete h;
         return -3;
     }

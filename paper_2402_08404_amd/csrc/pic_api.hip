@@ -51,8 +51,8 @@ const char* check_config(const pic_config* cfg) {
     if (!(cfg->phi_w > 0) || !(cfg->xi > 0) || !(cfg->m_ion > 0)) return "phi_w, xi, m_ion must be positive";
     if (!(cfg->laplace_rtol > 0) || !(cfg->step_rtol > 0) || cfg->step_maxit < 1) return "bad solver tolerances";
     if (cfg->sort_every < 0) return "sort_every must be >= 0";
-    if (cfg->stencil_blocks != 0 && (cfg->stencil_blocks < 64 || cfg->stencil_blocks > 2048))
-        return "stencil_blocks must be 0 or in 64..2048";
+    if (cfg->stencil_blocks != 0 && (cfg->stencil_blocks < 64 || cfg->stencil_blocks > 4096))
+        return "stencil_blocks must be 0 or in 64..4096";
     if (cfg->step_guess < 0 || cfg->step_guess > 1) return "step_guess must be 0 or 1";
     if (cfg->id_capacity < 0 || cfg->id_capacity > ((int64_t)1 << 32)) return "id_capacity out of range";
     return nullptr;

@@ -201,13 +201,16 @@ __device__ inline ZMarch zmarch(int nx, int ny, int nz, int kc) {
     return z;
 }
 
-// Grid of a z-marching launch of about `target` blocks; kc is rounded up to
-// a multiple of `align`.
+// Grid of a z-marching launch of about `target` blocks (at most
+// kMaxStencilBlocks where the grid allows); kc is rounded up to a multiple
+// of `align`.
+constexpr int kMaxStencilBlocks = 4096;
 inline unsigned zmarch_grid(int nx, int ny, int nz, int target, int align, int* kc) {
     int64_t cols = (int64_t)((nx + 63) / 64) * ((ny + 3) / 4);
     int64_t k = (nz * cols + target - 1) / target;
     if (k < 1) k = 1;
     k = (k + align - 1) / align * align;
+    while (k < nz && cols * ((nz + k - 1) / k) > kMaxStencilBlocks) k += align;  // partial-sum slots
     *kc = (int)k;
     return (unsigned)(cols * ((nz + k - 1) / k));
 }
