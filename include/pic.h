@@ -258,7 +258,9 @@ void pic_destroy(pic_ctx* ctx);
  *
  * Normalization. With q = rho 2^-40 (elementary charges per node) and
  * s = max |q|, the network maps x = q / s to y, and the guess is
- *   phi0 = V0 phi1 + (e s / (eps0 h)) y.
+ *   phi0 = V0 phi1 + (e s / (eps0 h)) y
+ * (or V0 phi1 + gamma y with the energy-norm weight gamma, see
+ * pic_set_learned_guess).
  * The charge part phi_rho = phi - V0 phi1 solves A phi_rho = q e / (eps0 h)
  * with zero on every fixed node, so y* = phi_rho eps0 h / (e s) solves A y* = x:
  * the target is dimensionless and of order one whatever the charge.
