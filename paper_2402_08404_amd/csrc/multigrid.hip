@@ -391,21 +391,63 @@ __device__ inline double row_dot(const MgLevel& L, const mgv* __restrict__ x, in
 
 // One damped Jacobi sweep on a coarse level, xo = xi + omega D^-1 (b - A xi);
 // with RESID the residual b - A xi instead (zero where there is no unknown).
+// A wavefront covers a run of nodes of one plane, which holds only a few row
+// classes (the interior one and those of the faces it touches): the
+// wavefront copies each distinct row once into LDS (up to kSlots rows; the
+// slot stride is odd, so lanes of different slots read different banks) and
+// the lanes read their coefficients there. A wavefront with more classes
+// (near the tip) reads the rows from the table per lane.
+constexpr int kSlots = 8, kSlotStride = 129;
+
 template <bool RESID>
 __global__ __launch_bounds__(kBlock) void k_mg_sweep(MgArgs a, MgLevel L, const float* __restrict__ tab,
                                                       const mgv* __restrict__ xi, mgv* __restrict__ xo) {
+    __shared__ float slots[kBlock / 64][kSlots * kSlotStride];
     PlaneIdx q;
-    if (!plane_idx(L.nx, L.ny, q)) return;
+    const bool in = plane_idx(L.nx, L.ny, q);
+    if (!in) {  // lanes past the plane work on its last node and store nothing
+        q.p = L.nx * L.ny - 1;
+        q.j = L.ny - 1;
+        q.i = L.nx - 1;
+        q.n = (int64_t)q.k * L.nx * L.ny + q.p;
+    }
     const uint32_t cls = L.id[q.n];
     const double bn = L.b[q.n];
-    const double xn = xi[q.n];
+    const float xn = xi[q.n];
     if (a.s->done) return;
-    const float* t = tab + (size_t)cls * kTabRow;
-    const double ax = row_dot(L, xi, q.i, q.j, q.k, (float)xn, t);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    float* sw = slots[w];
+    // distinct classes of the wavefront, in order of their first lane
+    int slot = -1, ns = 0;
+    unsigned long long rem = __ballot(true);
+    while (rem && ns < kSlots) {
+        const int lead = __ffsll((long long)rem) - 1;
+        const uint32_t c = __shfl(cls, lead);
+        const unsigned long long m = __ballot(cls == c);
+        if (cls == c) slot = ns;
+        const float* src = tab + (size_t)c * kTabRow;
+        sw[ns * kSlotStride + lane] = src[lane];
+        sw[ns * kSlotStride + 64 + lane] = src[64 + lane];
+        rem &= ~m;
+        ++ns;
+    }
+    __builtin_amdgcn_wave_barrier();
+    double ax;
+    float invd;
+    if (rem == 0) {
+        const float* t = sw + slot * kSlotStride;
+        ax = row_dot(L, xi, q.i, q.j, q.k, xn, t);
+        invd = t[kTabInvD];
+    } else {
+        const float* t = tab + (size_t)cls * kTabRow;
+        ax = row_dot(L, xi, q.i, q.j, q.k, xn, t);
+        invd = t[kTabInvD];
+    }
+    if (!in) return;
     if (RESID)
         xo[q.n] = (mgv)((bn - ax) * (double)(cls != 0));
     else
-        xo[q.n] = (mgv)(xn + (double)t[kTabInvD] * (bn - ax));  // class 0: xn = 0, omega / D = 0
+        xo[q.n] = (mgv)((double)xn + (double)invd * (bn - ax));  // class 0: xn = 0, omega / D = 0
 }
 
 // b_c = P^T r for an even fine width (fnx = 2 C.nx): each lane reads its
