@@ -54,6 +54,8 @@ struct MgLevel {
     float* tab;     // levels >= 1: class table, kTabRow values per class
     int ncls;
     mgv *x0, *x1, *b;  // iterates and right-hand side (b: levels >= 1)
+    int zkc;           // planes per block of the z-marching sweep (0: plane kernel)
+    unsigned zblocks;
 };
 
 struct MgHier {
@@ -448,6 +450,137 @@ __global__ __launch_bounds__(kBlock) void k_mg_sweep(MgArgs a, MgLevel L, const 
         xo[q.n] = (mgv)((bn - ax) * (double)(cls != 0));
     else
         xo[q.n] = (mgv)((double)xn + (double)invd * (bn - ax));  // class 0: xn = 0, omega / D = 0
+}
+
+// The same sweep on a large coarse level as a z-marching kernel: a block is
+// a 16 x 16 (x, y) tile of columns walking kc planes, each wavefront an 8 x 8
+// patch of it. Each plane of xi is staged once in LDS with a halo of two
+// nodes (20 x 20 values, clamped at the grid faces where the coefficients are
+// zero) in a ring of six planes. A patch away from the faces and the tip
+// holds one row class: its coefficients are then wave-uniform (scalar
+// loads); other patches keep their classes in LDS slots as above, refreshed
+// when a plane brings another set of classes. One barrier per plane: step k
+// loads plane k + 2 into the slot of plane k - 4, which no thread reads after
+// step k - 2.
+constexpr int kZT = 16, kZH = kZT + 4, kZRing = 6, kZHalo = kZH * kZH;
+
+__device__ inline int zring(int k) { return (k + 2 * kZRing) % kZRing; }  // k >= -2
+
+inline unsigned zgrid16(int nx, int ny, int nz, int target, int* kc) {
+    const int64_t cols = (int64_t)((nx + kZT - 1) / kZT) * ((ny + kZT - 1) / kZT);
+    int64_t k = (nz * cols + target - 1) / target;
+    if (k < 1) k = 1;
+    *kc = (int)k;
+    return (unsigned)(cols * ((nz + k - 1) / k));
+}
+
+// sum_o t_o (x_o - x_c) + (sum_o t_o) x_c from the staged planes; (hx, hy)
+// is the node's position in the halo tile
+__device__ inline double ring_dot(const float (*sx)[kZHalo], int k, int hx, int hy, float xc,
+                                  const float* __restrict__ t) {
+    float s = 0.0f;
+#pragma unroll
+    for (int dz = 0; dz < 5; ++dz) {
+        const float* pln = sx[zring(k + dz - 2)];
+        float v[25];
+#pragma unroll
+        for (int q = 0; q < 25; ++q) v[q] = pln[(hy + q / 5 - 2) * kZH + hx + q % 5 - 2];
+#pragma unroll
+        for (int q = 0; q < 25; ++q) s = fmaf(t[25 * dz + q], v[q] - xc, s);
+    }
+    return (double)s + (double)t[kTabSum] * (double)xc;
+}
+
+template <bool RESID>
+__global__ __launch_bounds__(kBlock) void k_mg_sweep_z(MgArgs a, MgLevel L, const float* __restrict__ tab,
+                                                        const mgv* __restrict__ xi, mgv* __restrict__ xo, int kc) {
+    __shared__ float sx[kZRing][kZHalo];
+    __shared__ float slots[kBlock / 64][kSlots * kSlotStride];
+    if (a.s->done) return;  // the same for every thread of the block
+    const int ntx = (L.nx + kZT - 1) / kZT, nty = (L.ny + kZT - 1) / kZT;
+    const int64_t b = xcd_block(blockIdx.x, gridDim.x);
+    const int bx = (int)(b % ntx);
+    const int64_t rb = b / ntx;
+    const int by = (int)(rb % nty), bz = (int)(rb / nty);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tx = 8 * (w & 1) + (lane & 7), ty = 8 * (w >> 1) + (lane >> 3);  // position in the tile
+    const int x0 = bx * kZT, y0 = by * kZT;
+    const int i = x0 + tx, j = y0 + ty;
+    const bool col = i < L.nx && j < L.ny;
+    const int k0 = bz * kc, k1 = k0 + kc < L.nz ? k0 + kc : L.nz;
+    const int pl = L.nx * L.ny;
+    // halo values loaded by this thread: e = threadIdx.x + 256 q, e < 400
+    int off[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int e = (int)threadIdx.x + kBlock * q;
+        const int ee = e < kZHalo ? e : 0;
+        const int hy = ee / kZH, hx = ee - hy * kZH;
+        off[q] = clampi(y0 - 2 + hy, L.ny) * L.nx + clampi(x0 - 2 + hx, L.nx);
+    }
+    const bool second = (int)threadIdx.x + kBlock < kZHalo;
+    auto load = [&](int kk) {
+        float* dst = sx[zring(kk)];
+        const mgv* src = xi + (int64_t)clampi(kk, L.nz) * pl;
+        const float v0 = src[off[0]];
+        const float v1 = src[second ? off[1] : off[0]];
+        dst[threadIdx.x] = v0;
+        if (second) dst[threadIdx.x + kBlock] = v1;
+    };
+    for (int kk = k0 - 2; kk < k0 + 2; ++kk) load(kk);
+    const int ic = i < L.nx ? i : L.nx - 1, jc = j < L.ny ? j : L.ny - 1;
+    const int hx = tx + 2, hy = ty + 2;
+    float* sw = slots[w];
+    int slot = -1;
+    bool staged = false;  // the patch's classes are all in its slots
+    uint32_t prev = 0xFFFFFFFFu;
+    for (int k = k0; k < k1; ++k) {
+        load(k + 2);
+        const int64_t n = (int64_t)k * pl + jc * L.nx + ic;
+        const uint32_t cls = L.id[n];
+        const double bn = L.b[n];
+        __syncthreads();
+        const float xn = sx[zring(k)][hy * kZH + hx];
+        const uint32_t c0 = __builtin_amdgcn_readfirstlane(cls);
+        double ax;
+        float invd;
+        if (__all(cls == c0)) {
+            const float* tt = tab + (size_t)c0 * kTabRow;
+            ax = ring_dot(sx, k, hx, hy, xn, tt);
+            invd = tt[kTabInvD];
+        } else {
+            if (!__all(cls == prev)) {
+                slot = -1;
+                int ns = 0;
+                unsigned long long rem = __ballot(true);
+                while (rem && ns < kSlots) {
+                    const int lead = __ffsll((long long)rem) - 1;
+                    const uint32_t c = __shfl(cls, lead);
+                    const unsigned long long m = __ballot(cls == c);
+                    if (cls == c) slot = ns;
+                    const float* src = tab + (size_t)c * kTabRow;
+                    sw[ns * kSlotStride + lane] = src[lane];
+                    sw[ns * kSlotStride + 64 + lane] = src[64 + lane];
+                    rem &= ~m;
+                    ++ns;
+                }
+                staged = rem == 0;
+                prev = cls;
+                __builtin_amdgcn_wave_barrier();
+            }
+            if (staged) {
+                const float* tt = sw + slot * kSlotStride;
+                ax = ring_dot(sx, k, hx, hy, xn, tt);
+                invd = tt[kTabInvD];
+            } else {
+                const float* tt = tab + (size_t)cls * kTabRow;
+                ax = ring_dot(sx, k, hx, hy, xn, tt);
+                invd = tt[kTabInvD];
+            }
+        }
+        const mgv out = RESID ? (mgv)((bn - ax) * (double)(cls != 0)) : (mgv)((double)xn + (double)invd * (bn - ax));
+        if (col) xo[n] = out;
+    }
 }
 
 // b_c = P^T r for an even fine width (fnx = 2 C.nx): each lane reads its
@@ -876,6 +1009,10 @@ int mg_setup(pic_ctx* c) {
         L.n = (int64_t)L.nx * L.ny * L.nz;
         L.tab = nullptr;
         L.ncls = 0;
+        L.zkc = 0;
+        L.zblocks = 0;
+        if (l >= 1 && L.nx >= 32 && L.ny >= 32)
+            L.zblocks = zgrid16(L.nx, L.ny, L.nz, stencil_target(c), &L.zkc);
         if (l == 0) {
             L.id = nullptr;
             L.used = nullptr;
@@ -989,12 +1126,19 @@ float* mg_vcycle(pic_ctx* c, const TB* b0, double* part_rr, double* part_bb, dou
     mgv* res[kMgMaxLevels];      // final iterate per level
     // Jacobi sweep (resid = false) or residual (resid = true) on coarse level L
     auto sweep = [&](const MgLevel& L, bool resid, const mgv* xi, mgv* xo) {
-        if (resid)
-            hipLaunchKernelGGL(k_mg_sweep<true>, plane_grid(L), dim3(kBlock), 0, c->stream, a, L, (const float*)L.tab, xi,
-                               xo);
-        else
-            hipLaunchKernelGGL(k_mg_sweep<false>, plane_grid(L), dim3(kBlock), 0, c->stream, a, L, (const float*)L.tab,
-                               xi, xo);
+        const float* tab = L.tab;
+        if (L.zblocks) {
+            if (resid)
+                hipLaunchKernelGGL(k_mg_sweep_z<true>, dim3(L.zblocks), dim3(kBlock), 0, c->stream, a, L, tab, xi, xo,
+                                   L.zkc);
+            else
+                hipLaunchKernelGGL(k_mg_sweep_z<false>, dim3(L.zblocks), dim3(kBlock), 0, c->stream, a, L, tab, xi, xo,
+                                   L.zkc);
+        } else if (resid) {
+            hipLaunchKernelGGL(k_mg_sweep<true>, plane_grid(L), dim3(kBlock), 0, c->stream, a, L, tab, xi, xo);
+        } else {
+            hipLaunchKernelGGL(k_mg_sweep<false>, plane_grid(L), dim3(kBlock), 0, c->stream, a, L, tab, xi, xo);
+        }
     };
     // b of level l + 1 from the residual r of level l
     auto restrict_to = [&](int l, const mgv* r) {
