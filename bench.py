@@ -120,6 +120,26 @@ def pmc_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib, 
     return out
 
 
+def trace_summary(trace_csv, min_us=10.0):
+    """Per-launch durations of the step kernels from a rocprofv3 --kernel-trace
+    CSV: average over all launches and over the launches longer than min_us
+    (a solve replays its iterations in captured chunks, so some launches of the
+    solver kernels come after convergence and return at once)."""
+    import csv
+    import statistics
+    rows = list(csv.DictReader(open(trace_csv)))
+    res = {}
+    for sym in list(KERNEL_SYMBOLS.values()) + ["k_mcc_small<float>", "k_mg_sweep_z<false>"]:
+        name = "pic::" + sym
+        d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows
+             if r["Kernel_Name"].replace("void ", "").startswith(name + "(") or
+             r["Kernel_Name"].replace("void ", "") == name]
+        w = [x for x in d if x > min_us]
+        res[name] = {"launches": len(d), "avg_us": sum(d) / max(len(d), 1), "working": len(w),
+                     "working_avg_us": sum(w) / max(len(w), 1), "working_median_us": statistics.median(w) if w else 0.0}
+    return res
+
+
 def measured_traffic(kernel: str):
     """Scaled HBM bytes per launch of a kernel from the committed summary, or None."""
     sym = KERNEL_SYMBOLS.get(kernel)
@@ -195,6 +215,8 @@ def main():
     ap.add_argument("--pmc-summary", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV",
                                                         "COPY_MIB"),
                     help="write the HBM traffic summary of rocprofv3 --pmc runs to profiles/ and exit")
+    ap.add_argument("--trace-summary", metavar="KERNEL_TRACE_CSV",
+                    help="print the per-launch durations of the step kernels in a rocprofv3 kernel trace and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB five times (the reference kernel that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
@@ -208,6 +230,9 @@ def main():
         a = args.pmc_summary
         out = pmc_summary(a[0], a[1], a[2], a[3], float(a[4]), TRAFFIC_FILE)
         print(json.dumps({k: round(v["bytes"] / 1e6, 1) for k, v in out["kernels"].items()}, indent=1))
+        return
+    if args.trace_summary:
+        print(json.dumps(trace_summary(args.trace_summary), indent=1))
         return
     import torch
     if args.calibrate_copy:
@@ -301,10 +326,18 @@ def main():
     pb = push_bytes(ne_avg, nn, fp32)
     kernels = {"push_electrons": {"avg_ms": k_push_e, "launches": tm["push_e"][1], "bytes": pb,
                                   "gbs": pb / (k_push_e * 1e-3) / 1e9}}
+    # A solve launches its iterations in chunks, so some launches of the
+    # solver kernels come after convergence and return at once: each kernel's
+    # total event time is divided by the iterations that did work (the
+    # returning launches' few microseconds stay in the total, so the average
+    # errs high and the bandwidth low).
+    iters_prof = int(m2["cg_iters_total"] - it_p0)
     for name, per_node in SOLVER_BYTES_PER_NODE.items():
         b = per_node * nn
-        a_ms = avg(name)
-        kernels[name] = {"avg_ms": a_ms, "launches": tm[name][1], "bytes": b, "gbs": b / (a_ms * 1e-3) / 1e9}
+        n_work = iters_prof if 0 < iters_prof <= tm[name][1] else tm[name][1]
+        a_ms = tm[name][0] / n_work if n_work else float("nan")
+        kernels[name] = {"avg_ms": a_ms, "launches": n_work, "launches_total": tm[name][1], "bytes": b,
+                         "gbs": b / (a_ms * 1e-3) / 1e9}
     # dominant kernel: largest time summed over its launches in the profiled pass
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"]
               if kernels[k]["launches"] else -1.0)
