@@ -189,7 +189,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="gpu_scale", choices=["gpu_scale", "tiny"])
     ap.add_argument("--solver", default="mgcg", choices=["cg", "mgcg", "mixed"])
-    ap.add_argument("--sort-every", type=int, default=16)
+    ap.add_argument("--sort-every", type=int, default=0,
+                    help="reorder period of the particle arrays (0: the tuned value for this grid, else 16)")
     ap.add_argument("--stencil-blocks", type=int, default=0, help="override the tuned block count of the solver kernels")
     ap.add_argument("--step-guess", type=int, default=1, choices=[0, 1],
                     help="step-solve guess: 0 previous potential, 1 linear extrapolation in time")
@@ -265,6 +266,7 @@ def main():
     from paper_2402_08404_amd import batch as B
     tune = B.load_tuning(args.tuning).get(B.shape_key(cfg), {})
     stencil_blocks = int(args.stencil_blocks or tune.get("stencil_blocks", 0))
+    args.sort_every = int(args.sort_every or tune.get("sort_every", 16))
     sim = pic.Simulation(cfg, caps=caps, precision=pic.PIC_F32 if fp32 else pic.PIC_F64, solver=solver,
                          step_rtol=1e-8, step_maxit=20000, sort_every=args.sort_every, stencil_blocks=stencil_blocks,
                          step_guess=args.step_guess)

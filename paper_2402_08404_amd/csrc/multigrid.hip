@@ -21,8 +21,9 @@
 //
 // Smoother: damped Jacobi, the same number of sweeps before and after the
 // coarse correction (the first from zero), so the V-cycle is a symmetric
-// positive definite preconditioner for CG. The coarsest level (at most 1024
-// nodes) is solved exactly with its inverse, formed once on the host.
+// positive definite preconditioner for CG. The coarsest level (at most
+// kCoarseMax nodes) is solved exactly with its inverse, formed once at set-up
+// on the device (Gauss-Jordan in FP64) and stored in FP32.
 #include <cmath>
 #include <cstring>
 #include <unordered_map>
@@ -33,6 +34,7 @@
 namespace pic {
 
 constexpr int kMgMaxLevels = 12;
+constexpr int64_t kCoarseMax = 2048;  // nodes of the coarsest level at most
 
 // Storage of every multigrid vector and coarse coefficient: FP32 (the V-cycle
 // is a preconditioner, so its precision decides only how good the search
@@ -62,7 +64,7 @@ struct MgHier {
     int nlev;
     MgLevel lv[kMgMaxLevels];
     mgv* z[2];     // finest-level iterates (ping-pong)
-    double* cinv;  // inverse of the coarsest operator, n x n (zero rows / columns for non-unknowns)
+    float* cinv;   // inverse of the coarsest operator, n x n (zero rows / columns for non-unknowns)
     int pre, post; // sweeps on the coarse levels (the finest level always does two and two)
     int zm_kc;     // planes per block of the fine sweeps
     unsigned zm_blocks;
@@ -73,7 +75,10 @@ static void mg_dims(const pic_config* cfg, std::vector<int3>& dims) {
     dims.push_back(make_int3(nx, ny, nz));
     while ((int)dims.size() < kMgMaxLevels) {
         int3 d = dims.back();
-        if ((int64_t)d.x * d.y * d.z <= 512 || d.x <= 2 || d.y <= 2 || d.z <= 2) break;
+        const int64_t n = (int64_t)d.x * d.y * d.z;
+        // stop at the first coarse level of at most kCoarseMax nodes (a
+        // finest grid of at most 512 nodes gets no coarse level)
+        if ((n <= kCoarseMax && (dims.size() > 1 || n <= 512)) || d.x <= 2 || d.y <= 2 || d.z <= 2) break;
         dims.push_back(make_int3((d.x + 1) / 2, (d.y + 1) / 2, (d.z + 1) / 2));
     }
 }
@@ -89,7 +94,7 @@ size_t mg_bytes(const pic_config* cfg) {
         b += (size_t)n * (4 + 1 + 3 * sizeof(mgv)) + 5 * 256;
     }
     int64_t nc = (int64_t)dims.back().x * dims.back().y * dims.back().z;
-    if (nc <= 1024) b += (size_t)nc * nc * 8 + 256;
+    if (nc <= kCoarseMax) b += (size_t)nc * nc * 4 + 256;
     return b;
 }
 
@@ -350,17 +355,6 @@ __device__ inline bool plane_idx(int nx, int ny, PlaneIdx& q) {
     return true;
 }
 
-// First sweep from x = 0 on a coarse level: x = omega D^-1 b (zero where
-// there is no unknown: its table row holds omega / D = 0).
-__global__ __launch_bounds__(kBlock) void k_mg_first(MgArgs a, MgLevel L, const float* __restrict__ tab) {
-    PlaneIdx q;
-    if (!plane_idx(L.nx, L.ny, q)) return;
-    const uint32_t cls = L.id[q.n];
-    const double bn = L.b[q.n];
-    if (a.s->done) return;
-    L.x0[q.n] = (mgv)((double)tab[(size_t)cls * kTabRow + kTabInvD] * bn);
-}
-
 // (row . x) at node (i, j, k) of a coarse level for the class row t
 // (coefficient index 25 (dz + 2) + 5 (dy + 2) + dx + 2), as
 // sum_o t_o (x_o - x_c) + (sum_o t_o) x_c: the differences of neighbouring
@@ -462,7 +456,9 @@ __global__ __launch_bounds__(kBlock) void k_mg_sweep(MgArgs a, MgLevel L, const 
 // when a plane brings another set of classes. One barrier per plane: step k
 // loads plane k + 2 into the slot of plane k - 4, which no thread reads after
 // step k - 2.
-constexpr int kZT = 16, kZH = kZT + 4, kZRing = 6, kZHalo = kZH * kZH;
+// An LDS plane holds kZH rows of kZH values at a row pitch of kZP floats:
+// with the pitch 24 the 8 rows of an 8 x 8 patch fall into distinct banks.
+constexpr int kZT = 16, kZH = kZT + 4, kZP = 24, kZRing = 6, kZHalo = kZH * kZH, kZPlane = kZH * kZP;
 
 __device__ inline int zring(int k) { return (k + 2 * kZRing) % kZRing; }  // k >= -2
 
@@ -476,7 +472,7 @@ inline unsigned zgrid16(int nx, int ny, int nz, int target, int* kc) {
 
 // sum_o t_o (x_o - x_c) + (sum_o t_o) x_c from the staged planes; (hx, hy)
 // is the node's position in the halo tile
-__device__ inline double ring_dot(const float (*sx)[kZHalo], int k, int hx, int hy, float xc,
+__device__ inline double ring_dot(const float (*sx)[kZPlane], int k, int hx, int hy, float xc,
                                   const float* __restrict__ t) {
     float s = 0.0f;
 #pragma unroll
@@ -484,7 +480,7 @@ __device__ inline double ring_dot(const float (*sx)[kZHalo], int k, int hx, int 
         const float* pln = sx[zring(k + dz - 2)];
         float v[25];
 #pragma unroll
-        for (int q = 0; q < 25; ++q) v[q] = pln[(hy + q / 5 - 2) * kZH + hx + q % 5 - 2];
+        for (int q = 0; q < 25; ++q) v[q] = pln[(hy + q / 5 - 2) * kZP + hx + q % 5 - 2];
 #pragma unroll
         for (int q = 0; q < 25; ++q) s = fmaf(t[25 * dz + q], v[q] - xc, s);
     }
@@ -494,7 +490,7 @@ __device__ inline double ring_dot(const float (*sx)[kZHalo], int k, int hx, int 
 template <bool RESID>
 __global__ __launch_bounds__(kBlock) void k_mg_sweep_z(MgArgs a, MgLevel L, const float* __restrict__ tab,
                                                         const mgv* __restrict__ xi, mgv* __restrict__ xo, int kc) {
-    __shared__ float sx[kZRing][kZHalo];
+    __shared__ float sx[kZRing][kZPlane];
     __shared__ float slots[kBlock / 64][kSlots * kSlotStride];
     if (a.s->done) return;  // the same for every thread of the block
     const int ntx = (L.nx + kZT - 1) / kZT, nty = (L.ny + kZT - 1) / kZT;
@@ -510,24 +506,37 @@ __global__ __launch_bounds__(kBlock) void k_mg_sweep_z(MgArgs a, MgLevel L, cons
     const int k0 = bz * kc, k1 = k0 + kc < L.nz ? k0 + kc : L.nz;
     const int pl = L.nx * L.ny;
     // halo values loaded by this thread: e = threadIdx.x + 256 q, e < 400
-    int off[2];
+    int off[2], doff[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int e = (int)threadIdx.x + kBlock * q;
         const int ee = e < kZHalo ? e : 0;
         const int hy = ee / kZH, hx = ee - hy * kZH;
         off[q] = clampi(y0 - 2 + hy, L.ny) * L.nx + clampi(x0 - 2 + hx, L.nx);
+        doff[q] = hy * kZP + hx;
     }
     const bool second = (int)threadIdx.x + kBlock < kZHalo;
-    auto load = [&](int kk) {
-        float* dst = sx[zring(kk)];
+    // plane kk (clamped into the grid) into registers, and from there into
+    // its ring slot
+    auto fetch = [&](int kk, float& v0, float& v1) {
         const mgv* src = xi + (int64_t)clampi(kk, L.nz) * pl;
-        const float v0 = src[off[0]];
-        const float v1 = src[second ? off[1] : off[0]];
-        dst[threadIdx.x] = v0;
-        if (second) dst[threadIdx.x + kBlock] = v1;
+        v0 = src[off[0]];
+        v1 = src[second ? off[1] : off[0]];
     };
-    for (int kk = k0 - 2; kk < k0 + 2; ++kk) load(kk);
+    auto put = [&](int kk, float v0, float v1) {
+        float* dst = sx[zring(kk)];
+        dst[doff[0]] = v0;
+        if (second) dst[doff[1]] = v1;
+    };
+    for (int kk = k0 - 2; kk < k0 + 2; ++kk) {
+        float v0, v1;
+        fetch(kk, v0, v1);
+        put(kk, v0, v1);
+    }
+    // plane k + 2 is fetched during the step before k, so its loads are in
+    // flight while that step computes
+    float pv0, pv1;
+    fetch(k0 + 2, pv0, pv1);
     const int ic = i < L.nx ? i : L.nx - 1, jc = j < L.ny ? j : L.ny - 1;
     const int hx = tx + 2, hy = ty + 2;
     float* sw = slots[w];
@@ -535,12 +544,13 @@ __global__ __launch_bounds__(kBlock) void k_mg_sweep_z(MgArgs a, MgLevel L, cons
     bool staged = false;  // the patch's classes are all in its slots
     uint32_t prev = 0xFFFFFFFFu;
     for (int k = k0; k < k1; ++k) {
-        load(k + 2);
+        put(k + 2, pv0, pv1);
         const int64_t n = (int64_t)k * pl + jc * L.nx + ic;
         const uint32_t cls = L.id[n];
         const double bn = L.b[n];
+        fetch(k + 3, pv0, pv1);  // issued after this step's id and b, so waiting for those leaves it in flight
         __syncthreads();
-        const float xn = sx[zring(k)][hy * kZH + hx];
+        const float xn = sx[zring(k)][hy * kZP + hx];
         const uint32_t c0 = __builtin_amdgcn_readfirstlane(cls);
         double ax;
         float invd;
@@ -583,13 +593,23 @@ __global__ __launch_bounds__(kBlock) void k_mg_sweep_z(MgArgs a, MgLevel L, cons
     }
 }
 
+// Stores the restricted residual b of coarse node n and, when first is set,
+// also the first pre-smoothing sweep from x = 0, x = omega D^-1 b (from the
+// FP32 value of b; zero where there is no unknown, whose table row holds
+// omega / D = 0).
+__device__ inline void store_restricted(const MgLevel& C, int64_t n, double s, int first) {
+    const mgv bn = (mgv)s;
+    C.b[n] = bn;
+    if (first) C.x0[n] = (mgv)((double)C.tab[(size_t)C.id[n] * kTabRow + kTabInvD] * (double)bn);
+}
+
 // b_c = P^T r for an even fine width (fnx = 2 C.nx): each lane reads its
 // two fine nodes 2J, 2J+1 of a row as one float2 and 2J-1, 2J+2 as single
 // values (clamped at the row ends, where their weight is zero); every load is
 // unconditional, so all 48 are in flight together. Row sums in FP32 (weights
 // 1/4, 3/4, 1), the y and z sums in FP64.
 __global__ __launch_bounds__(kBlock) void k_mg_restrict2(MgArgs a, int fnx, int fny, int fnz, const mgv* __restrict__ r,
-                                                          MgLevel C) {
+                                                          MgLevel C, int first) {
     PlaneIdx q;
     if (!plane_idx(C.nx, C.ny, q)) return;
     const int Jx = q.i, Jy = q.j, Jz = q.k;
@@ -635,13 +655,13 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict2(MgArgs a, int fnx, int 
     }
     const uint8_t u = C.used[q.n];
     if (a.s->done) return;
-    C.b[q.n] = (mgv)(s * (double)u);
+    store_restricted(C, q.n, s * (double)u, first);
 }
 
 // b_c = P^T r: coarse node J collects the fine nodes 2J-1 .. 2J+2 of each
 // axis with their interpolation weights (zero where J is not an unknown).
 __global__ __launch_bounds__(kBlock) void k_mg_restrict(MgArgs a, int fnx, int fny, int fnz, const mgv* __restrict__ r,
-                                                         MgLevel C) {
+                                                         MgLevel C, int first) {
     PlaneIdx q;
     if (!plane_idx(C.nx, C.ny, q)) return;
     const int Jx = q.i, Jy = q.j, Jz = q.k;
@@ -674,7 +694,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(MgArgs a, int fnx, int f
         s += wz[dz] * sy;
     }
     if (a.s->done) return;
-    C.b[q.n] = (mgv)(s * (double)u);
+    store_restricted(C, q.n, s * (double)u, first);
 }
 
 // xo = xi + P xc on a level of fnx x fny x fnz nodes (zero where the node is
@@ -751,14 +771,29 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong2(MgArgs a, int fnx, int f
     *(float2*)(xo + n) = out;
 }
 
-// Coarsest level: x = A^-1 b with the stored inverse, one wavefront per row.
-__global__ __launch_bounds__(kBlock) void k_mg_coarsest(MgArgs a, MgLevel L, const double* __restrict__ inv) {
+// Coarsest level: x = A^-1 b with the stored inverse, one wavefront per row
+// (16-byte loads when the row length is a multiple of 4; rows and b start on
+// 256-byte boundaries).
+__global__ __launch_bounds__(kBlock) void k_mg_coarsest(MgArgs a, MgLevel L, const float* __restrict__ inv) {
     if (a.s->done) return;
-    int64_t row = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    int lane = threadIdx.x & 63;
-    if (row >= L.n) return;
+    const int row = (int)(blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6));
+    const int lane = threadIdx.x & 63;
+    const int n = (int)L.n;
+    if (row >= n) return;
+    const float* r = inv + (size_t)row * n;
     double acc = 0.0;
-    for (int64_t c = lane; c < L.n; c += 64) acc += inv[row * L.n + c] * (double)L.b[c];
+    if ((n & 3) == 0) {
+        const float4* r4 = (const float4*)r;
+        const float4* b4 = (const float4*)L.b;
+#pragma unroll 8
+        for (int c = lane; c < (n >> 2); c += 64) {
+            const float4 w = r4[c], v = b4[c];
+            acc += (double)w.x * v.x + (double)w.y * v.y + (double)w.z * v.z + (double)w.w * v.w;
+        }
+    } else {
+#pragma unroll 8
+        for (int c = lane; c < n; c += 64) acc += (double)r[c] * (double)L.b[c];
+    }
     acc = wave_sum(acc);
     if (lane == 0) L.x0[row] = (mgv)acc;
 }
@@ -876,22 +911,21 @@ static dim3 plane_grid(int nx, int ny, int nz) {
 }
 static dim3 plane_grid(const MgLevel& L) { return plane_grid(L.nx, L.ny, L.nz); }
 
-// Inverse of the coarsest operator (n <= 1024) by Cholesky factorization on
-// the host (upper triangle of the stored rows); rows and columns of nodes
-// without an unknown stay zero.
-static int coarsest_inverse(const MgLevel& L, const std::vector<float>& rows, std::vector<double>& inv) {
+// The coarsest operator as a dense n x n FP64 matrix (row-major) from its
+// stored rows; a node without an unknown (zero row) gets a unit row and
+// column, so the matrix is symmetric positive definite and its inverse keeps
+// those nodes apart. act[I] = 1 for a node with an unknown.
+static int coarsest_dense(const MgLevel& L, const std::vector<float>& rows, std::vector<double>& A,
+                          std::vector<uint8_t>& act) {
     const int64_t n = L.n;
-    std::vector<int> act;
-    std::vector<int> pos(n, -1);
-    for (int64_t I = 0; I < n; ++I)
-        if (rows[(size_t)I * 125 + kCenter] != 0.0f) {
-            pos[I] = (int)act.size();
-            act.push_back((int)I);
+    act.assign(n, 0);
+    for (int64_t I = 0; I < n; ++I) act[I] = rows[(size_t)I * 125 + kCenter] != 0.0f;
+    A.assign((size_t)n * n, 0.0);
+    for (int64_t I = 0; I < n; ++I) {
+        if (!act[I]) {
+            A[(size_t)I * n + I] = 1.0;
+            continue;
         }
-    const int m = (int)act.size();
-    std::vector<double> A((size_t)m * m, 0.0);
-    for (int r = 0; r < m; ++r) {
-        const int64_t I = act[r];
         const int i = (int)(I % L.nx), j = (int)((I / L.nx) % L.ny), k = (int)(I / ((int64_t)L.nx * L.ny));
         for (int o = 0; o < 125; ++o) {
             const float v = rows[(size_t)I * 125 + o];
@@ -899,40 +933,103 @@ static int coarsest_inverse(const MgLevel& L, const std::vector<float>& rows, st
             const int ii = i + o % 5 - 2, jj = j + (o / 5) % 5 - 2, kk = k + o / 25 - 2;
             if (ii < 0 || ii >= L.nx || jj < 0 || jj >= L.ny || kk < 0 || kk >= L.nz) return -3;
             const int64_t K = ((int64_t)kk * L.ny + jj) * L.nx + ii;
-            if (pos[K] < 0) return -3;
-            A[(size_t)r * m + pos[K]] = v;
+            if (!act[K]) return -3;
+            A[(size_t)I * n + K] = v;
         }
-    }
-    // A = R^T R (upper R in place)
-    for (int c = 0; c < m; ++c) {
-        double d = A[(size_t)c * m + c];
-        for (int t = 0; t < c; ++t) d -= A[(size_t)t * m + c] * A[(size_t)t * m + c];
-        if (!(d > 0.0)) return -3;
-        d = std::sqrt(d);
-        A[(size_t)c * m + c] = d;
-        for (int col = c + 1; col < m; ++col) {
-            double v = A[(size_t)c * m + col];
-            for (int t = 0; t < c; ++t) v -= A[(size_t)t * m + c] * A[(size_t)t * m + col];
-            A[(size_t)c * m + col] = v / d;
-        }
-    }
-    inv.assign((size_t)n * n, 0.0);
-    std::vector<double> y(m);
-    for (int e = 0; e < m; ++e) {
-        // R^T y = e_e, then R x = y
-        for (int r = 0; r < m; ++r) {
-            double v = (r == e) ? 1.0 : 0.0;
-            for (int t = 0; t < r; ++t) v -= A[(size_t)t * m + r] * y[t];
-            y[r] = v / A[(size_t)r * m + r];
-        }
-        for (int r = m - 1; r >= 0; --r) {
-            double v = y[r];
-            for (int t = r + 1; t < m; ++t) v -= A[(size_t)r * m + t] * y[t];
-            y[r] = v / A[(size_t)r * m + r];
-        }
-        for (int r = 0; r < m; ++r) inv[(size_t)act[r] * n + act[e]] = y[r];
     }
     return 0;
+}
+
+// In-place Gauss-Jordan inversion of a symmetric positive definite n x n
+// matrix, one pivot p per pair of launches (no pivot search: the pivots are
+// the positive leading Schur complements). k_gj_save copies row p and column
+// p, k_gj_step then applies
+//   A[p][p] <- 1 / a,  A[p][j] <- A[p][j] / a,  A[i][p] <- -A[i][p] / a,
+//   A[i][j] <- A[i][j] - A[i][p] A[p][j] / a    (a = A[p][p], i, j != p);
+// after the last pivot A holds the inverse. A pivot that is not positive sets
+// *bad.
+__global__ __launch_bounds__(kBlock) void k_gj_save(const double* __restrict__ A, int n, int p, double* __restrict__ col,
+                                                     double* __restrict__ row) {
+    const int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (t >= n) return;
+    col[t] = A[(size_t)t * n + p];
+    row[t] = A[(size_t)p * n + t];
+}
+
+__global__ __launch_bounds__(kBlock) void k_gj_step(double* __restrict__ A, int n, int p, const double* __restrict__ col,
+                                                     const double* __restrict__ row, int* __restrict__ bad) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * n) return;
+    const double a = row[p];
+    if (!(a > 0.0)) {
+        if (e == 0) *bad = 1;
+        return;
+    }
+    const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+    const double d = 1.0 / a;
+    double v;
+    if (i == p)
+        v = j == p ? d : row[j] * d;
+    else if (j == p)
+        v = -col[i] * d;
+    else
+        v = A[e] - col[i] * row[j] * d;
+    A[e] = v;
+}
+
+// inv = the symmetric part of the FP64 inverse in FP32, zero in the rows and
+// columns of nodes without an unknown
+__global__ __launch_bounds__(kBlock) void k_gj_store(const double* __restrict__ A, int n, const uint8_t* __restrict__ act,
+                                                      float* __restrict__ inv) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n * n) return;
+    const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+    const double v = 0.5 * (A[e] + A[(size_t)j * n + i]);
+    inv[e] = (act[i] && act[j]) ? (float)v : 0.0f;
+}
+
+// h->cinv = inverse of the coarsest operator L (rows: its stored rows).
+static int coarsest_inverse(pic_ctx* c, const MgLevel& L, const std::vector<float>& rows, float* cinv) {
+    std::vector<double> A;
+    std::vector<uint8_t> act;
+    if (coarsest_dense(L, rows, A, act) != 0) return -3;
+    const int n = (int)L.n;
+    const size_t nn = (size_t)n * n;
+    // work buffer: the matrix, row and column of the pivot, the flag, the mask
+    char* w = nullptr;
+    const size_t off_col = nn * 8, off_row = off_col + (size_t)n * 8, off_bad = off_row + (size_t)n * 8,
+                 off_act = off_bad + 256, bytes = off_act + (size_t)n;
+    if (hipMalloc((void**)&w, bytes) != hipSuccess) return -2;
+    double* Ad = (double*)w;
+    double* col = (double*)(w + off_col);
+    double* row = (double*)(w + off_row);
+    int* bad = (int*)(w + off_bad);
+    uint8_t* actd = (uint8_t*)(w + off_act);
+    int rc = 0;
+    int bad_h = 0;
+    if (hipMemcpyAsync(Ad, A.data(), nn * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(actd, act.data(), (size_t)n, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(bad, &bad_h, sizeof(int), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+        rc = -2;
+    const unsigned gs = (unsigned)((n + kBlock - 1) / kBlock), ge = (unsigned)((nn + kBlock - 1) / kBlock);
+    for (int p = 0; p < n && rc == 0; ++p) {
+        hipLaunchKernelGGL(k_gj_save, dim3(gs), dim3(kBlock), 0, c->stream, (const double*)Ad, n, p, col, row);
+        hipLaunchKernelGGL(k_gj_step, dim3(ge), dim3(kBlock), 0, c->stream, Ad, n, p, (const double*)col,
+                           (const double*)row, bad);
+    }
+    if (rc == 0) {
+        hipLaunchKernelGGL(k_gj_store, dim3(ge), dim3(kBlock), 0, c->stream, (const double*)Ad, n,
+                           (const uint8_t*)actd, cinv);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(&bad_h, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            rc = -2;
+        else if (bad_h)
+            rc = -3;
+    }
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(w);
+    return rc;
 }
 
 // Classes of identical rows: ids[n] (0 for the zero row of a node without an
@@ -995,7 +1092,7 @@ int mg_setup(pic_ctx* c) {
     MgHier* h = new MgHier();
     h->nlev = (int)dims.size();
     int64_t nn = c->g.nn;
-    if (h->nlev < 2 || (int64_t)dims.back().x * dims.back().y * dims.back().z > 1024) {
+    if (h->nlev < 2 || (int64_t)dims.back().x * dims.back().y * dims.back().z > kCoarseMax) {
         delete h;
         return -3;
     }
@@ -1028,7 +1125,7 @@ int mg_setup(pic_ctx* c) {
         L.b = (mgv*)take(L.n * sizeof(mgv));
     }
     MgLevel& Lc = h->lv[h->nlev - 1];
-    h->cinv = (double*)take((size_t)Lc.n * Lc.n * 8);
+    h->cinv = (float*)take((size_t)Lc.n * Lc.n * 4);
     h->pre = 2;
     h->post = 2;
     h->zm_blocks = zmarch_grid(c->g.nx, c->g.ny, c->g.nz, stencil_target(c), 1, &h->zm_kc);
@@ -1046,7 +1143,6 @@ int mg_setup(pic_ctx* c) {
     std::vector<float> rows;
     std::vector<uint32_t> ids;
     std::vector<float> tab;
-    std::vector<double> inv;
     int rc = 0;
     for (int l = 1; l < h->nlev && rc == 0; ++l) {
         MgLevel& F = h->lv[l - 1];
@@ -1085,15 +1181,7 @@ int mg_setup(pic_ctx* c) {
             rc = -2;
             break;
         }
-        if (l == h->nlev - 1) {
-            if (coarsest_inverse(C, rows, inv) != 0) {
-                rc = -3;
-                break;
-            }
-            if (hipMemcpyAsync(h->cinv, inv.data(), inv.size() * 8, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-                hipStreamSynchronize(c->stream) != hipSuccess)
-                rc = -2;
-        }
+        if (l == h->nlev - 1) rc = coarsest_inverse(c, C, rows, h->cinv);
     }
     (void)hipFree(rows_d);
     if (rc != 0) {
@@ -1141,13 +1229,18 @@ float* mg_vcycle(pic_ctx* c, const TB* b0, double* part_rr, double* part_bb, dou
         }
     };
     // b of level l + 1 from the residual r of level l
+    // (and, on a level that is not the coarsest, its first pre-smoothing
+    // sweep from zero)
     auto restrict_to = [&](int l, const mgv* r) {
         const MgLevel& F = h->lv[l];
         const MgLevel& C = h->lv[l + 1];
+        const int first = l + 1 < nl - 1 ? 1 : 0;
         if (F.nx % 2 == 0)
-            hipLaunchKernelGGL(k_mg_restrict2, plane_grid(C), dim3(kBlock), 0, c->stream, a, F.nx, F.ny, F.nz, r, C);
+            hipLaunchKernelGGL(k_mg_restrict2, plane_grid(C), dim3(kBlock), 0, c->stream, a, F.nx, F.ny, F.nz, r, C,
+                               first);
         else
-            hipLaunchKernelGGL(k_mg_restrict, plane_grid(C), dim3(kBlock), 0, c->stream, a, F.nx, F.ny, F.nz, r, C);
+            hipLaunchKernelGGL(k_mg_restrict, plane_grid(C), dim3(kBlock), 0, c->stream, a, F.nx, F.ny, F.nz, r, C,
+                               first);
     };
     hipLaunchKernelGGL(k_mg_test, dim3(1), dim3(kBlock), 0, c->stream, a, cg_blocks);
     // finest level: two sweeps from zero, the residual, its restriction
@@ -1167,9 +1260,7 @@ float* mg_vcycle(pic_ctx* c, const TB* b0, double* part_rr, double* part_bb, dou
     // coarse levels down: pre-smoothing, residual, restriction
     for (int l = 1; l < nl - 1; ++l) {
         MgLevel& L = h->lv[l];
-        const float* tab = L.tab;
-        hipLaunchKernelGGL(k_mg_first, plane_grid(L), dim3(kBlock), 0, c->stream, a, L, tab);
-        mgv* cur = L.x0;
+        mgv* cur = L.x0;  // the first sweep, written by the restriction
         mgv* oth = L.x1;
         for (int s = 1; s < h->pre; ++s) {
             sweep(L, false, cur, oth);
@@ -1182,7 +1273,7 @@ float* mg_vcycle(pic_ctx* c, const TB* b0, double* part_rr, double* part_bb, dou
         pre_out[l] = cur;
     }
     hipLaunchKernelGGL(k_mg_coarsest, dim3((unsigned)((h->lv[nl - 1].n + 3) / 4)), dim3(kBlock), 0, c->stream, a,
-                       h->lv[nl - 1], (const double*)h->cinv);
+                       h->lv[nl - 1], (const float*)h->cinv);
     res[nl - 1] = h->lv[nl - 1].x0;
     // coarse levels up: correction, post-smoothing
     for (int l = nl - 2; l >= 1; --l) {
