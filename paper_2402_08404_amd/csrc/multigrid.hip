@@ -470,19 +470,25 @@ inline unsigned zgrid16(int nx, int ny, int nz, int target, int* kc) {
     return (unsigned)(cols * ((nz + k - 1) / k));
 }
 
-// sum_o t_o (x_o - x_c) + (sum_o t_o) x_c from the staged planes; (hx, hy)
-// is the node's position in the halo tile
-__device__ inline double ring_dot(const float (*sx)[kZPlane], int k, int hx, int hy, float xc,
-                                  const float* __restrict__ t) {
+// sum_o t_o (x_o - x_c) + (sum_o t_o) x_c from the staged planes; lb is the
+// offset of the node's 5 x 5 window (its corner) in a plane
+__device__ inline double ring_dot(const float (*sx)[kZPlane], int k, int lb, float xc, const float* __restrict__ t) {
     float s = 0.0f;
 #pragma unroll
     for (int dz = 0; dz < 5; ++dz) {
-        const float* pln = sx[zring(k + dz - 2)];
-        float v[25];
+        // one address per plane, the 25 reads at constant offsets from it
+        // (the empty asm keeps the compiler from hoisting 25 per-lane
+        // addresses out of the loop and adding the plane base to each)
+        int a = lb;
+        asm volatile("" : "+v"(a));
+        const float* pln = sx[zring(k + dz - 2)] + a;
+        float c[25], v[25];
 #pragma unroll
-        for (int q = 0; q < 25; ++q) v[q] = pln[(hy + q / 5 - 2) * kZP + hx + q % 5 - 2];
+        for (int q = 0; q < 25; ++q) c[q] = t[25 * dz + q];
 #pragma unroll
-        for (int q = 0; q < 25; ++q) s = fmaf(t[25 * dz + q], v[q] - xc, s);
+        for (int q = 0; q < 25; ++q) v[q] = pln[(q / 5) * kZP + q % 5];
+#pragma unroll
+        for (int q = 0; q < 25; ++q) s = fmaf(c[q], v[q] - xc, s);
     }
     return (double)s + (double)t[kTabSum] * (double)xc;
 }
@@ -490,8 +496,10 @@ __device__ inline double ring_dot(const float (*sx)[kZPlane], int k, int hx, int
 template <bool RESID>
 __global__ __launch_bounds__(kBlock) void k_mg_sweep_z(MgArgs a, MgLevel L, const float* __restrict__ tab,
                                                         const mgv* __restrict__ xi, mgv* __restrict__ xo, int kc) {
-    __shared__ float sx[kZRing][kZPlane];
-    __shared__ float slots[kBlock / 64][kSlots * kSlotStride];
+    // one LDS array, the plane ring first: a plane's 25 reads then fit in the
+    // offset fields of the read instructions from one address
+    __shared__ float lds[kZRing * kZPlane + (kBlock / 64) * kSlots * kSlotStride];
+    float(*sx)[kZPlane] = (float(*)[kZPlane])lds;
     if (a.s->done) return;  // the same for every thread of the block
     const int ntx = (L.nx + kZT - 1) / kZT, nty = (L.ny + kZT - 1) / kZT;
     const int64_t b = xcd_block(blockIdx.x, gridDim.x);
@@ -528,27 +536,36 @@ __global__ __launch_bounds__(kBlock) void k_mg_sweep_z(MgArgs a, MgLevel L, cons
         dst[doff[0]] = v0;
         if (second) dst[doff[1]] = v1;
     };
-    for (int kk = k0 - 2; kk < k0 + 2; ++kk) {
-        float v0, v1;
-        fetch(kk, v0, v1);
-        put(kk, v0, v1);
-    }
-    // plane k + 2 is fetched during the step before k, so its loads are in
-    // flight while that step computes
+    const int ic = i < L.nx ? i : L.nx - 1, jc = j < L.ny ? j : L.ny - 1;
+    const int64_t n0 = (int64_t)k0 * pl + jc * L.nx + ic;
+    // Every value a step needs is loaded during the step before it: plane
+    // k + 2 of the ring, the class id and b of node k. The first planes and
+    // step are all issued before the first wait.
+    float pro[4][2];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) fetch(k0 - 2 + q, pro[q][0], pro[q][1]);
     float pv0, pv1;
     fetch(k0 + 2, pv0, pv1);
-    const int ic = i < L.nx ? i : L.nx - 1, jc = j < L.ny ? j : L.ny - 1;
+    uint32_t cls_next = L.id[n0];
+    float b_next = L.b[n0];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) put(k0 - 2 + q, pro[q][0], pro[q][1]);
     const int hx = tx + 2, hy = ty + 2;
-    float* sw = slots[w];
+    const int lb = (hy - 2) * kZP + hx - 2;  // the node's 5 x 5 window in a plane
+    float* sw = lds + kZRing * kZPlane + w * (kSlots * kSlotStride);
     int slot = -1;
     bool staged = false;  // the patch's classes are all in its slots
     uint32_t prev = 0xFFFFFFFFu;
     for (int k = k0; k < k1; ++k) {
         put(k + 2, pv0, pv1);
         const int64_t n = (int64_t)k * pl + jc * L.nx + ic;
-        const uint32_t cls = L.id[n];
-        const double bn = L.b[n];
-        fetch(k + 3, pv0, pv1);  // issued after this step's id and b, so waiting for those leaves it in flight
+        const uint32_t cls = cls_next;
+        const double bn = (double)b_next;
+        // the next step's loads (at the last step, node k again)
+        const int64_t nn = k + 1 < k1 ? n + pl : n;
+        fetch(k + 3, pv0, pv1);
+        cls_next = L.id[nn];
+        b_next = L.b[nn];
         __syncthreads();
         const float xn = sx[zring(k)][hy * kZP + hx];
         const uint32_t c0 = __builtin_amdgcn_readfirstlane(cls);
@@ -556,7 +573,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_sweep_z(MgArgs a, MgLevel L, cons
         float invd;
         if (__all(cls == c0)) {
             const float* tt = tab + (size_t)c0 * kTabRow;
-            ax = ring_dot(sx, k, hx, hy, xn, tt);
+            ax = ring_dot(sx, k, lb, xn, tt);
             invd = tt[kTabInvD];
         } else {
             if (!__all(cls == prev)) {
@@ -580,11 +597,11 @@ __global__ __launch_bounds__(kBlock) void k_mg_sweep_z(MgArgs a, MgLevel L, cons
             }
             if (staged) {
                 const float* tt = sw + slot * kSlotStride;
-                ax = ring_dot(sx, k, hx, hy, xn, tt);
+                ax = ring_dot(sx, k, lb, xn, tt);
                 invd = tt[kTabInvD];
             } else {
                 const float* tt = tab + (size_t)cls * kTabRow;
-                ax = ring_dot(sx, k, hx, hy, xn, tt);
+                ax = ring_dot(sx, k, lb, xn, tt);
                 invd = tt[kTabInvD];
             }
         }
