@@ -41,7 +41,18 @@ constexpr int64_t kCoarseMax = 2048;  // nodes of the coarsest level at most
 // directions are; the Krylov vectors, dot products and the convergence test
 // stay FP64). Arithmetic inside the kernels is FP64.
 typedef float mgv;
-constexpr double kOmega = 6.0 / 7.0;    // damped Jacobi weight, 7-point finest operator
+// Finest level: two Jacobi sweeps before and after the coarse correction with
+// the weights 1 / theta_1, 1 / theta_2, theta_i the roots of the degree-2
+// Chebyshev polynomial on [0.4, 2] (the eigenvalues of D^-1 A of the 7-point
+// operator lie in [0, 2]): the pair multiplies the error components with
+// eigenvalues in [0.4, 2] by at most 1 / T_2(1.5) = 0.29 per smoothing,
+// against 0.51 for two sweeps with the weight 6/7, and every component with
+// an eigenvalue in (0, 2] by less than 1. The two sweeps commute, so the
+// V-cycle stays symmetric (before: omega_1 then omega_2; after: omega_2 then
+// omega_1).
+constexpr double kChebMid = 1.2, kChebHalf = 0.8, kSqrtHalf = 0.70710678118654752;
+constexpr double kOmega1 = 1.0 / (kChebMid + kChebHalf * kSqrtHalf);  // 0.5664
+constexpr double kOmega2 = 1.0 / (kChebMid - kChebHalf * kSqrtHalf);  // 1.5765
 constexpr double kOmegaC = 0.7;         // damped Jacobi weight, 125-point coarse operators
 constexpr int kTabRow = 128;            // table row: 125 coefficients, omega / D, row sum
 constexpr int kTabInvD = 125;
@@ -298,32 +309,32 @@ struct MgArgs {
     double* part_rr;   // CG partials of r.r (finest level, read by the first kernel)
     double* part_bb;   // CG partials of b.b (read before the first iteration)
     double* part_rz;   // partials of r.z written by the last kernel
+    int cg_blocks;     // number of CG partials
 };
 
-// Convergence test of the CG update (one block): finishes r.r (and b.b
-// before the first iteration) and sets done.
-__global__ void k_mg_test(MgArgs a, int cg_blocks) {
+// Convergence test of the CG update, taken by every block of the first
+// kernel of the V-cycle: finishes r.r (and b.b before the first iteration)
+// from the CG partials in a fixed order, so every block gets the same
+// answer; block 0 stores it (and sets done on convergence). All threads of
+// the block must call it.
+__device__ inline bool mg_test(const MgArgs& a) {
     DevState* s = a.s;
-    if (s->done) return;
-    double rr = sum_partials_n(a.part_rr, cg_blocks);
-    double bb;
-    if (s->it == 0) {
-        bb = sum_partials_n(a.part_bb, cg_blocks);
-        if (threadIdx.x == 0) {
+    const double rr = sum_partials_n(a.part_rr, a.cg_blocks);
+    const bool first = s->it == 0;
+    const double bb = first ? sum_partials_n(a.part_bb, a.cg_blocks) : s->bb;
+    const bool conv = (bb == 0.0) || (sqrt(rr) <= s->rtol * sqrt(bb)) || (s->it >= s->maxit);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (first) {
             s->bb = bb;
             s->rr0 = rr;
         }
-    } else {
-        bb = s->bb;
-    }
-    bool conv = (bb == 0.0) || (sqrt(rr) <= s->rtol * sqrt(bb)) || (s->it >= s->maxit);
-    if (threadIdx.x == 0) {
         s->rr = rr;
         if (conv) {
             s->done = 1;
             s->zero_solution = (bb == 0.0);
         }
     }
+    return conv;
 }
 
 // Coarse-level kernels run on a grid of (plane tiles, planes): a block is a
@@ -826,10 +837,10 @@ __device__ inline double fine_diag(const Grid& g, int i, int j, int k) {
 }
 
 // Input value of a fine kernel at node m:
-//   kFineFirst: the first sweep from zero, omega b / D (b is zero on fixed nodes);
+//   kFineFirst: the first sweep from zero, omega_1 b / D (b is zero on fixed nodes);
 //   kFinePlain, kFineResid: xi (zero on fixed nodes).
 // The diagonal of a free node does not depend on k (free nodes are never on
-// a z face), so kFineFirst takes omega / D of the node's column, cw.
+// a z face), so kFineFirst takes omega_1 / D of the node's column, cw.
 constexpr int kFinePlain = 0, kFineFirst = 1, kFineResid = 3;
 
 template <int MODE, typename TB>
@@ -843,19 +854,22 @@ struct FineIn {
 };
 
 // omega / D for a free node of column (i, j) (zero outside the grid)
-__device__ inline double col_weight(const Grid& g, int i, int j) {
+__device__ inline double col_weight(const Grid& g, int i, int j, double omega) {
     if (i < 0 || i >= g.nx || j < 0 || j >= g.ny) return 0.0;
-    return kOmega / fine_diag(g, i, j, 1 < g.nz - 1 ? 1 : 0);
+    return omega / fine_diag(g, i, j, 1 < g.nz - 1 ? 1 : 0);
 }
 
-// One damped Jacobi sweep on the finest level (kFineFirst: two sweeps from
-// zero; kFineResid: the residual b - A xi instead); with LAST the partials of
-// r.z (b . xo) are written, one per block.
+// One damped Jacobi sweep on the finest level with the weight w_out
+// (kFineFirst: the convergence test of the CG update, then two sweeps from
+// zero, the first with the weight w_in; kFineResid: the residual b - A xi
+// instead); with LAST the partials of r.z (b . xo) are written, one per
+// block.
 template <int MODE, bool LAST, typename TB>
 __global__ __launch_bounds__(kBlock) void k_mg_fine_sweep(MgArgs a, const TB* __restrict__ b0, const mgv* __restrict__ xi,
-                                                           mgv* __restrict__ xo, int kc) {
+                                                           mgv* __restrict__ xo, int kc, double w_out, double w_in) {
     DevState* s = a.s;
     if (s->done) return;
+    if (MODE == kFineFirst && mg_test(a)) return;
     const Grid& g = a.g;
     FineIn<MODE, TB> in{xi, b0};
     ZMarch t = zmarch(g.nx, g.ny, g.nz, kc);
@@ -865,12 +879,14 @@ __global__ __launch_bounds__(kBlock) void k_mg_fine_sweep(MgArgs a, const TB* __
         int64_t pl = (int64_t)g.nx * g.ny;
         int64_t n = (int64_t)t.k0 * pl + (int64_t)j * g.nx + i;
         double hx = hedge(i, g.nx), hy = hedge(j, g.ny), fz = hx * hy;
-        double cw = col_weight(g, i, j), cwW = 0.0, cwE = 0.0, cwS = 0.0, cwN = 0.0;
+        const double cwo = col_weight(g, i, j, w_out);
+        double cw = 0.0, cwW = 0.0, cwE = 0.0, cwS = 0.0, cwN = 0.0;
         if (MODE == kFineFirst) {
-            cwW = col_weight(g, i - 1, j);
-            cwE = col_weight(g, i + 1, j);
-            cwS = col_weight(g, i, j - 1);
-            cwN = col_weight(g, i, j + 1);
+            cw = col_weight(g, i, j, w_in);
+            cwW = col_weight(g, i - 1, j, w_in);
+            cwE = col_weight(g, i + 1, j, w_in);
+            cwS = col_weight(g, i, j - 1, w_in);
+            cwN = col_weight(g, i, j + 1, w_in);
         }
         // neighbours outside the grid are read at the node itself (every load
         // is unconditional, so a step's loads are issued together) and given
@@ -899,7 +915,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_fine_sweep(MgArgs a, const TB* __
             acc += wn * (vc - xn);
             acc += fz * (vc - vm);
             acc += fz * (vc - vp);
-            const double v = MODE == kFineResid ? bn - acc : vc + cw * (bn - acc);
+            const double v = MODE == kFineResid ? bn - acc : vc + cwo * (bn - acc);
             const mgv out = (mgv)(v * (double)fr);  // values are finite
             if (LAST) rz += bn * (double)out;
             xo[n] = out;
@@ -1225,6 +1241,7 @@ float* mg_vcycle(pic_ctx* c, const TB* b0, double* part_rr, double* part_bb, dou
     a.part_rr = part_rr;
     a.part_bb = part_bb;
     a.part_rz = part_rz;
+    a.cg_blocks = cg_blocks;
     const int nl = h->nlev;
     const Grid& g = c->g;
     mgv* pre_out[kMgMaxLevels];  // pre-smoothed iterate per level
@@ -1259,17 +1276,17 @@ float* mg_vcycle(pic_ctx* c, const TB* b0, double* part_rr, double* part_bb, dou
             hipLaunchKernelGGL(k_mg_restrict, plane_grid(C), dim3(kBlock), 0, c->stream, a, F.nx, F.ny, F.nz, r, C,
                                first);
     };
-    hipLaunchKernelGGL(k_mg_test, dim3(1), dim3(kBlock), 0, c->stream, a, cg_blocks);
-    // finest level: two sweeps from zero, the residual, its restriction
+    // finest level: the convergence test and two sweeps from zero, the
+    // residual, its restriction
     {
         MgLevel& L = h->lv[0];
         int t1 = timed ? tic(c, PIC_T_MG_FIRST) : -1;
         hipLaunchKernelGGL((k_mg_fine_sweep<kFineFirst, false, TB>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream, a,
-                           b0, (const mgv*)nullptr, L.x0, h->zm_kc);
+                           b0, (const mgv*)nullptr, L.x0, h->zm_kc, kOmega2, kOmega1);
         toc(c, t1);
         int t2 = timed ? tic(c, PIC_T_MG_RESTRICT) : -1;
         hipLaunchKernelGGL((k_mg_fine_sweep<kFineResid, false, TB>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream, a,
-                           b0, (const mgv*)L.x0, L.x1, h->zm_kc);
+                           b0, (const mgv*)L.x0, L.x1, h->zm_kc, 0.0, 0.0);
         toc(c, t2);
         restrict_to(0, (const mgv*)L.x1);
         pre_out[0] = L.x0;
@@ -1318,10 +1335,10 @@ float* mg_vcycle(pic_ctx* c, const TB* b0, double* part_rr, double* part_bb, dou
                            g.nz, (const uint8_t*)c->buf.node_type, (const mgv*)L.x0, L.x1, h->lv[1], (const mgv*)res[1]);
     toc(c, t3);
     hipLaunchKernelGGL((k_mg_fine_sweep<kFinePlain, false, TB>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream, a, b0,
-                       (const mgv*)L.x1, L.x0, h->zm_kc);
+                       (const mgv*)L.x1, L.x0, h->zm_kc, kOmega2, 0.0);
     int t4 = timed ? tic(c, PIC_T_MG_LAST) : -1;
     hipLaunchKernelGGL((k_mg_fine_sweep<kFinePlain, true, TB>), dim3(h->zm_blocks), dim3(kBlock), 0, c->stream, a, b0,
-                       (const mgv*)L.x0, L.x1, h->zm_kc);
+                       (const mgv*)L.x0, L.x1, h->zm_kc, kOmega1, 0.0);
     toc(c, t4);
     *n_rz = (int)h->zm_blocks;
     return L.x1;
