@@ -29,6 +29,9 @@ struct PushArgs {
     int64_t* rho;
     int64_t sign;
     uint32_t* key;
+    uint32_t* cnt;   // particles per cell key (nkeys entries), incremented here
+    uint32_t* rank;  // rank of each slot among the particles of its cell key
+    uint32_t nkeys;
     DevState* st;
     uint32_t step;
     uint64_t seed;
@@ -75,15 +78,21 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs<T> a) {
     // counted per thread, reduced per block (one atomic per block and kind)
     unsigned int lost[5] = {0, 0, 0, 0, 0};
     unsigned int bsi = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    // Every wavefront runs the loop the same number of times (lanes past the
+    // last slot load the last slot and store nothing), so that all lanes take
+    // part in the count of the keys.
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
+        const int64_t i = base + threadIdx.x;
+        const bool valid = i < n;
+        const int64_t il = valid ? i : n - 1;
         // The id and the state are loaded together and free slots go through
         // the same arithmetic (their results are not stored), so no branch
         // separates the loads: one memory latency for the state, one for the
         // gathered field.
-        const uint32_t id = a.s.id[i];
-        T X = a.s.x[i], Y = a.s.y[i], Z = a.s.z[i];
-        T VX = a.s.vx[i], VY = a.s.vy[i], VZ = a.s.vz[i];
-        const bool alive = id != kDead;
+        const uint32_t id = a.s.id[il];
+        T X = a.s.x[il], Y = a.s.y[il], Z = a.s.z[il];
+        T VX = a.s.vx[il], VY = a.s.vy[il], VZ = a.s.vz[il];
+        const bool alive = valid && id != kDead;
         if (MOVE) {
             if (SP != PIC_NEUTRAL) {
                 T ex, ey, ez;
@@ -102,7 +111,12 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs<T> a) {
         const int cj = clampi((int)floor(Yd), 0, g.ny - 2);
         const int ck = clampi((int)floor(Zd), 0, g.nz - 2);
         const bool keep = alive && code == 0;
-        a.key[i] = keep ? cell_key(g, ci, cj, ck) : kDead;
+        const uint32_t key = keep ? cell_key(g, ci, cj, ck) : kDead;
+        const uint32_t rk = count_key(a.cnt, a.nkeys, key);
+        if (valid) {
+            a.key[i] = key;
+            a.rank[i] = rk;
+        }
         if (!alive) continue;
         if (MOVE) {
             if (SP != PIC_NEUTRAL) {
@@ -978,6 +992,9 @@ static hipError_t particles_t(pic_ctx* c, bool move) {
     const pic_config& cf = c->cfg;
     hipLaunchKernelGGL(k_step_reset, dim3(1), dim3(1), 0, c->stream, c->st);
     (void)launch_zero(c->buf.rho, sizeof(int64_t) * c->g.nn, c->stream);
+    // the pushes count the particles per cell key into off (see cell_bins)
+    hipError_t ez = launch_zero(c->off, ((size_t)c->g.nkeys + 1) * 4, c->stream);
+    if (ez != hipSuccess) return ez;
     for (int s = 0; s < 3; ++s) {
         PushArgs<T> a;
         a.s = species<T>(c, s);
@@ -987,6 +1004,9 @@ static hipError_t particles_t(pic_ctx* c, bool move) {
         a.rho = c->buf.rho;
         a.sign = s == PIC_ELECTRON ? -1 : 1;
         a.key = c->key[s];
+        a.cnt = c->off;
+        a.rank = c->rank + (s >= 1 ? c->buf.cap[0] : 0) + (s == 2 ? c->buf.cap[1] : 0);
+        a.nkeys = (uint32_t)c->g.nkeys;
         a.st = c->st;
         a.step = (uint32_t)c->step;
         a.seed = cf.seed;

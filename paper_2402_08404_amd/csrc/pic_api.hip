@@ -103,7 +103,6 @@ size_t pic::scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[
     t->off = (uint32_t*)take((nc + 1) * 4);
     for (int s = 0; s < 3; ++s) t->key[s] = (uint32_t*)take(cap[s] * 4);
     t->bins = (uint32_t*)take(capsum * 4);
-    t->cursor = (uint32_t*)take((nc + 1) * 4);
     t->big = (uint32_t*)take(nc * 4);
     t->fi_list = (uint32_t*)take(cap[2] * 4);
     t->push_part = (uint32_t*)take(8192 * 8 * 4);

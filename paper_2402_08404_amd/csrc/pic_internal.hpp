@@ -176,6 +176,44 @@ __device__ inline int64_t xcd_block(int64_t b, int64_t G) {
     return x * per + (x < rem ? x : rem) + t;
 }
 
+// Runs of equal keys inside a wavefront: the run's first lane (head), the
+// run length (at the head) and every lane's offset inside its run.
+struct Run {
+    bool head;
+    int first, len;
+};
+
+__device__ inline Run wave_run(uint32_t k) {
+    const int lane = threadIdx.x & 63;
+    const uint32_t kp = __shfl_up(k, 1);
+    const bool head = lane == 0 || k != kp;
+    const unsigned long long heads = __ballot(head);
+    Run r;
+    r.head = head;
+    // first = the highest head at or below this lane
+    const unsigned long long below = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1));
+    r.first = 63 - __clzll(below);
+    // len (valid at a head) = distance to the next head, or to the wave end
+    const unsigned long long above = lane == 63 ? 0ull : (heads & ~((2ull << lane) - 1));
+    const int next = above ? __ffsll((long long)above) - 1 : 64;
+    r.len = next - lane;
+    return r;
+}
+
+// cnt[k] += 1 for the key k of every lane (keys >= nkeys count nothing), one
+// atomic per run of equal keys; every lane of the wavefront takes part.
+// Returns the lane's rank among the keys k counted so far (the count before
+// its run plus its place in the run), so a key's ranks are 0 .. cnt[k] - 1
+// once every lane has counted; undefined for keys that count nothing.
+__device__ inline uint32_t count_key(uint32_t* cnt, uint32_t nkeys, uint32_t k) {
+    if (k >= nkeys) k = kDead;
+    const Run r = wave_run(k);
+    uint32_t base = 0;
+    if (r.head && k != kDead) base = atomicAdd(&cnt[k], (uint32_t)r.len);
+    base = __shfl(base, r.first);
+    return base + (uint32_t)((int)(threadIdx.x & 63) - r.first);
+}
+
 // z-marching tiles for stencils on a node grid: blocks of 64 x 4 threads over
 // (x, y) (block index remapped so that consecutive tiles share an XCD), each
 // thread walking kc consecutive planes of one (x, y) column. Values of the
@@ -322,7 +360,6 @@ struct pic_ctx {
     uint32_t* off = nullptr;      // nkeys + 1
     uint32_t* key[3] = {};
     uint32_t* bins = nullptr;     // sum cap
-    uint32_t* cursor = nullptr;   // per-key scatter cursors of the cell bins (nkeys + 1)
     uint32_t* big = nullptr;      // big-cell list (nkeys)
     uint32_t* fi_list = nullptr;  // cap neutral
     uint32_t* push_part = nullptr;  // per-block partials of the push kernels (8192 x 8)
