@@ -293,6 +293,8 @@ struct MccArgs {
     uint32_t* bins;
     int64_t nc;  // number of cell keys
     uint32_t* big;
+    uint32_t* mcc_list;   // small cells for the full collision pass, one segment per scanning wavefront
+    uint32_t* mcc_count;  // cells in each wavefront's segment
     DevState* st;
     uint32_t step;
     uint64_t seed;
@@ -542,29 +544,96 @@ __device__ inline void mcc_cell(const MccArgs<T>& a, uint32_t c, uint32_t o0, in
     cell_class_seq(a, 2, c, kk, ee, ne, ni, ne + ni, nn, used, cnt, pn[1]);
 }
 
-// Cells with 2 .. kSmallCell particles, one lane each; larger cells are
-// queued for the wavefront kernel. Most cells hold fewer than two particles,
-// so each wavefront scans its own range of cells 64 at a time and gathers
-// the cells with work in a queue in LDS (ballot and prefix count), then runs
-// 64 of them at once with every lane busy.
+// Whether a cell of 2 .. kSmallCell particles can have a collision: some
+// projectile of class 1 or 2 draws below P_null. The null-collision draw of a
+// projectile depends only on its id, the step and the class (not on the
+// pairing), so a cell where every projectile draws a null collision has no
+// event and leaves every state unchanged (the full pass would skip each of
+// its pairs); the test ignores the neutrals already used by class 1, so it
+// may list a cell that then has no event, never the reverse.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_mcc_small(MccArgs<T> a) {
-    // P_null by class and target count, once per block
-    __shared__ double pn[2][kSmallCell + 1];
-    __shared__ uint32_t queue[kBlock / 64][128];
+__device__ inline bool mcc_probe(const MccArgs<T>& a, uint32_t o0, int n, const double (*pn)[kSmallCell + 1]) {
+    uint32_t e[kSmallCell], id[kSmallCell];
+#pragma unroll
+    for (int t = 0; t < kSmallCell; ++t) e[t] = a.bins[o0 + (t < n ? t : 0)];
+    int cs[3] = {0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < kSmallCell; ++t) {
+        const uint32_t sp = e[t] >> 30, slot = e[t] & 0x3FFFFFFFu;
+        const uint32_t* ids = sp == 0 ? a.sp[0].id : (sp == 1 ? a.sp[1].id : a.sp[2].id);
+        id[t] = ids[slot];
+        if (t < n) cs[sp] += 1;
+    }
+    // projectiles of each class as bit masks over the cell's entries
+    uint32_t pm[2] = {0u, 0u};
+    double pnull[2] = {0.0, 0.0};
+#pragma unroll
+    for (int cls = 1; cls <= 2; ++cls) {
+        const int na = cs[cls - 1], nb = cs[2];
+        if (na == 0 || nb == 0) continue;
+        const bool a_proj = na <= nb;
+        const uint32_t psp = a_proj ? (uint32_t)(cls - 1) : 2u;
+        pnull[cls - 1] = pn[cls - 1][a_proj ? nb : na];
+#pragma unroll
+        for (int t = 0; t < kSmallCell; ++t)
+            if (t < n && (e[t] >> 30) == psp) pm[cls - 1] |= 1u << t;
+    }
+    // one draw per projectile (class 1 first), until one is below P_null
+#pragma unroll 1
+    while (pm[0] | pm[1]) {
+        const int cls = pm[0] ? 1 : 2;
+        const int t = __ffs(cls == 1 ? pm[0] : pm[1]) - 1;
+        if (cls == 1)
+            pm[0] &= pm[0] - 1u;
+        else
+            pm[1] &= pm[1] - 1u;
+        uint32_t pid = id[0];
+#pragma unroll
+        for (int u = 1; u < kSmallCell; ++u) pid = t == u ? id[u] : pid;
+        const Draw2 d = draw2(a.seed, pid, a.step, cls == 1 ? kTagMcc1 : kTagMcc2, 0);
+        if (d.a < (cls == 1 ? pnull[0] : pnull[1])) return true;
+    }
+    return false;
+}
+
+// P_null by class and target count (the same in every block)
+template <typename T>
+__device__ inline void pnull_table(const MccArgs<T>& a, double (*pn)[kSmallCell + 1]) {
     if (threadIdx.x < 2 * (kSmallCell + 1)) {
         const int cls = 1 + (int)threadIdx.x / (kSmallCell + 1), nt = (int)threadIdx.x % (kSmallCell + 1);
         pn[cls - 1][nt] = nt > 0 ? pnull_of(a, cls, nt) : 0.0;
     }
     __syncthreads();
-    int cnt[5] = {0, 0, 0, 0, 0};
+}
+
+// The range of cells of scanning wavefront gw of nw: [cb, ce).
+__device__ inline void mcc_range(int64_t nc, int64_t nw, int64_t gw, int64_t& cb, int64_t& ce) {
+    const int64_t per = ((nc + nw - 1) / nw + 63) / 64 * 64;
+    cb = gw * per;
+    ce = cb + per < nc ? cb + per : nc;
+}
+
+// Cells with 2 .. kSmallCell particles: each wavefront scans its own range
+// of cells 64 at a time and gathers the cells with 2 .. kSmallCell particles
+// in a queue in LDS (ballot and prefix count; most cells hold fewer than
+// two), then tests 64 of them at once with every lane busy, and lists those
+// that can have a collision (all of them when the sorted order is to be
+// written back) in its own segment of the list (the part of the list from
+// the first cell of its range on; no counter shared between wavefronts).
+// Larger cells are listed for k_mcc_big.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mcc_small(MccArgs<T> a) {
+    __shared__ double pn[2][kSmallCell + 1];
+    __shared__ uint32_t queue[kBlock / 64][128];
+    pnull_table(a, pn);
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t* q = queue[w];
     const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
     const int64_t gw = (int64_t)blockIdx.x * (kBlock / 64) + w;
-    const int64_t per = ((a.nc + nw - 1) / nw + 63) / 64 * 64;
-    const int64_t cb = gw * per, ce = cb + per < a.nc ? cb + per : a.nc;
-    int qn = 0;  // the same in every lane
+    int64_t cb, ce;
+    mcc_range(a.nc, nw, gw, cb, ce);
+    int qn = 0;        // the same in every lane
+    uint32_t nl = 0;   // cells listed so far (the same in every lane)
     int64_t c0 = cb;
     while (c0 < ce || qn > 0) {
         while (qn < 64 && c0 < ce) {
@@ -587,11 +656,16 @@ __global__ __launch_bounds__(kBlock) void k_mcc_small(MccArgs<T> a) {
         }
         __builtin_amdgcn_wave_barrier();
         const int take = qn < 64 ? qn : 64;
+        uint32_t c = 0;
+        bool full = false;
         if (lane < take) {
-            const uint32_t c = q[lane];
+            c = q[lane];
             const uint32_t o0 = a.off[c];
-            mcc_cell(a, c, o0, (int)(a.off[c + 1] - o0), pn, cnt);
+            full = a.write_sorted || mcc_probe(a, o0, (int)(a.off[c + 1] - o0), pn);
         }
+        const unsigned long long fm = __ballot(full);
+        if (full) a.mcc_list[cb + nl + __popcll(fm & ((1ull << lane) - 1ull))] = c;
+        nl += (uint32_t)__popcll(fm);
         // move the cells not taken to the front of the queue
         const int rest = qn - take;
         const uint32_t keep = lane < rest ? q[take + lane] : 0u;
@@ -599,6 +673,28 @@ __global__ __launch_bounds__(kBlock) void k_mcc_small(MccArgs<T> a) {
         if (lane < rest) q[lane] = keep;
         __builtin_amdgcn_wave_barrier();
         qn = rest;
+    }
+    if (lane == 0 && gw < nw) a.mcc_count[gw] = nl;
+}
+
+// Collisions of the cells listed by k_mcc_small (launched with the same
+// grid): wavefront gw takes the segment of scanning wavefront gw, one lane
+// per cell.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mcc_cells(MccArgs<T> a) {
+    __shared__ double pn[2][kSmallCell + 1];
+    pnull_table(a, pn);
+    int cnt[5] = {0, 0, 0, 0, 0};
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+    const int64_t gw = (int64_t)blockIdx.x * (kBlock / 64) + w;
+    int64_t cb, ce;
+    mcc_range(a.nc, nw, gw, cb, ce);
+    const uint32_t nl = a.mcc_count[gw];
+    for (uint32_t t = (uint32_t)lane; t < nl; t += 64) {
+        const uint32_t c = a.mcc_list[cb + t];
+        const uint32_t o0 = a.off[c];
+        mcc_cell(a, c, o0, (int)(a.off[c + 1] - o0), pn, cnt);
     }
     flush_counts<T>(a.st, cnt);
 }
@@ -1061,6 +1157,8 @@ static hipError_t collide_t(pic_ctx* c, bool record) {
     a.bins = c->bins;
     a.nc = g.nkeys;
     a.big = c->big;
+    a.mcc_list = c->mcc_list;
+    a.mcc_count = c->mcc_count;
     a.st = c->st;
     a.step = (uint32_t)c->step;
     a.seed = cf.seed;
@@ -1084,7 +1182,11 @@ static hipError_t collide_t(pic_ctx* c, bool record) {
     a.record = record ? 1 : 0;
     a.write_sorted = resort ? 1 : 0;
     int tm = tic(c, PIC_T_MCC);
-    hipLaunchKernelGGL(k_mcc_small<T>, dim3(grid_for(g.nkeys)), dim3(kBlock), 0, c->stream, a);
+    // the two kernels take the same grid (a wavefront of the second reads the
+    // segment of the same wavefront of the first)
+    const unsigned gm = grid_for(g.nkeys);
+    hipLaunchKernelGGL(k_mcc_small<T>, dim3(gm), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(k_mcc_cells<T>, dim3(gm), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(k_mcc_big<T>, dim3(1024), dim3(64), 0, c->stream, a);
     toc(c, tm);
     hipLaunchKernelGGL(k_fi_resolve<T>, dim3(grid_for(c->buf.cap[2])), dim3(kBlock), 0, c->stream, a, c->fi_list,

@@ -104,6 +104,8 @@ size_t pic::scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[
     for (int s = 0; s < 3; ++s) t->key[s] = (uint32_t*)take(cap[s] * 4);
     t->bins = (uint32_t*)take(capsum * 4);
     t->big = (uint32_t*)take(nc * 4);
+    t->mcc_list = (uint32_t*)take(nc * 4);
+    t->mcc_count = (uint32_t*)take(4 * 8192 * 4);
     t->fi_list = (uint32_t*)take(cap[2] * 4);
     t->push_part = (uint32_t*)take(8192 * 8 * 4);
     t->nflag = (uint32_t*)take(cap[2] * 4);

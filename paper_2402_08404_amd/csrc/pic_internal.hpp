@@ -361,6 +361,8 @@ struct pic_ctx {
     uint32_t* key[3] = {};
     uint32_t* bins = nullptr;     // sum cap
     uint32_t* big = nullptr;      // big-cell list (nkeys)
+    uint32_t* mcc_list = nullptr;   // small cells for the full collision pass (nkeys)
+    uint32_t* mcc_count = nullptr;  // cells per scanning wavefront (4 x 8192)
     uint32_t* fi_list = nullptr;  // cap neutral
     uint32_t* push_part = nullptr;  // per-block partials of the push kernels (8192 x 8)
     uint32_t* nflag = nullptr;    // cap neutral: step+1 if the neutral had an event
