@@ -294,15 +294,16 @@ struct MccArgs {
     int64_t nc;  // number of cell keys
     uint32_t* big;
     uint32_t* mcc_list;   // small cells for the full collision pass, one segment per scanning wavefront
-    uint32_t* mcc_count;  // cells in each wavefront's segment
+    uint32_t* mcc_count;  // cells in each wavefront's segment (then their exclusive prefix sums)
+    uint32_t* mcc_dense;  // the listed cells of all segments, in segment order
+    const uint32_t* mcc_total;  // number of listed cells
     DevState* st;
     uint32_t step;
     uint64_t seed;
     double h, dt, m_ion, xi;
-    const double* xs;   // el, iz, cx tables
+    const double* xs;   // el, iz, cx tables, then the rate bounds of the two pair classes
     int xs_n;
     double xs_emin, xs_lnr;
-    double xs_max[2];
     uint32_t* nflag;
     uint32_t* bitmap_imp;
     uint32_t* prod_list;
@@ -454,12 +455,32 @@ __device__ int resolve_pair(const MccArgs<T>& a, int cls, uint32_t pid, uint32_t
     return PIC_EV_IONIZE;
 }
 
+// P_null of class cls for NT targets: an upper bound of the collision
+// probability of every pair of the class this step, from the largest
+// relative speed U (the largest speeds of the two species, rounded up) and
+// the bound of u sigma_tot(E(u)) over u <= U (the table entry one segment
+// above that of E(U), against rounding in the index; above the last node
+// sigma is the last value).
 template <typename T>
 __device__ inline double pnull_of(const MccArgs<T>& a, int cls, int NT) {
-    int sa = cls == 1 ? PIC_ELECTRON : PIC_ION;
-    double umax = ((double)__uint_as_float(a.st->smax_bits[sa]) + (double)__uint_as_float(a.st->smax_bits[2])) *
-                  (1.0 + 0x1p-20);
-    double x = umax * (double)NT * a.xs_max[cls - 1] / (a.h * a.h) * (1.0 + 1e-9);
+    const int sa = cls == 1 ? PIC_ELECTRON : PIC_ION;
+    const double ug = ((double)__uint_as_float(a.st->smax_bits[sa]) + (double)__uint_as_float(a.st->smax_bits[2])) *
+                      (1.0 + 0x1p-20);
+    const double U = ug * a.h / a.dt;
+    const double m = cls == 1 ? kMe : a.m_ion;
+    const double E = 0.5 * m * U * U / kQe;
+    const int n = a.xs_n;
+    const double* nu = a.xs + (size_t)(2 + cls) * n;
+    double rate;
+    if (E >= a.xs_emin * exp(a.xs_lnr)) {
+        const double slast = cls == 1 ? a.xs[n - 1] + a.xs[2 * n - 1] : a.xs[3 * n - 1];
+        rate = fmax(nu[n - 1], U * slast);
+    } else {
+        int k = E <= a.xs_emin ? 0 : (int)floor(log(E / a.xs_emin) / a.xs_lnr * (double)(n - 1));
+        k = k + 1 > n - 1 ? n - 1 : (k + 1 < 0 ? 0 : k + 1);
+        rate = nu[k];
+    }
+    const double x = rate * (double)NT / (a.h * a.h * a.h) * a.dt * (1.0 + 1e-9);
     return -expm1(-x);
 }
 
@@ -677,22 +698,32 @@ __global__ __launch_bounds__(kBlock) void k_mcc_small(MccArgs<T> a) {
     if (lane == 0 && gw < nw) a.mcc_count[gw] = nl;
 }
 
-// Collisions of the cells listed by k_mcc_small (launched with the same
-// grid): wavefront gw takes the segment of scanning wavefront gw, one lane
-// per cell.
+// The segments of k_mcc_small (launched with the same grid) copied one
+// after another into mcc_dense: wavefront gw copies its segment to the
+// prefix sum of the counts before it.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_mcc_cells(MccArgs<T> a) {
-    __shared__ double pn[2][kSmallCell + 1];
-    pnull_table(a, pn);
-    int cnt[5] = {0, 0, 0, 0, 0};
+__global__ __launch_bounds__(kBlock) void k_mcc_compact(MccArgs<T> a) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
     const int64_t gw = (int64_t)blockIdx.x * (kBlock / 64) + w;
     int64_t cb, ce;
     mcc_range(a.nc, nw, gw, cb, ce);
-    const uint32_t nl = a.mcc_count[gw];
-    for (uint32_t t = (uint32_t)lane; t < nl; t += 64) {
-        const uint32_t c = a.mcc_list[cb + t];
+    const uint32_t o = a.mcc_count[gw];
+    const uint32_t nl = (gw + 1 < nw ? a.mcc_count[gw + 1] : *a.mcc_total) - o;
+    for (uint32_t t = (uint32_t)lane; t < nl; t += 64) a.mcc_dense[o + t] = a.mcc_list[cb + t];
+}
+
+// Collisions of the listed cells, one lane per cell (every lane of a
+// wavefront busy but in the last one).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_mcc_cells(MccArgs<T> a) {
+    __shared__ double pn[2][kSmallCell + 1];
+    pnull_table(a, pn);
+    int cnt[5] = {0, 0, 0, 0, 0};
+    const int64_t nl = (int64_t)*a.mcc_total;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nl; t += stride) {
+        const uint32_t c = a.mcc_dense[t];
         const uint32_t o0 = a.off[c];
         mcc_cell(a, c, o0, (int)(a.off[c + 1] - o0), pn, cnt);
     }
@@ -1159,6 +1190,8 @@ static hipError_t collide_t(pic_ctx* c, bool record) {
     a.big = c->big;
     a.mcc_list = c->mcc_list;
     a.mcc_count = c->mcc_count;
+    a.mcc_dense = c->mcc_dense;
+    a.mcc_total = c->dyn + 8;
     a.st = c->st;
     a.step = (uint32_t)c->step;
     a.seed = cf.seed;
@@ -1170,8 +1203,6 @@ static hipError_t collide_t(pic_ctx* c, bool record) {
     a.xs_n = cf.xs_n;
     a.xs_emin = cf.xs_emin;
     a.xs_lnr = log(cf.xs_emax / cf.xs_emin);
-    a.xs_max[0] = c->xs_max[0];
-    a.xs_max[1] = c->xs_max[1];
     a.nflag = c->nflag;
     a.bitmap_imp = c->bitmap[0];
     a.prod_list = c->prod_list;
@@ -1182,11 +1213,14 @@ static hipError_t collide_t(pic_ctx* c, bool record) {
     a.record = record ? 1 : 0;
     a.write_sorted = resort ? 1 : 0;
     int tm = tic(c, PIC_T_MCC);
-    // the two kernels take the same grid (a wavefront of the second reads the
-    // segment of the same wavefront of the first)
+    // the scan and the compaction take the same grid (a wavefront of the
+    // second copies the segment of the same wavefront of the first)
     const unsigned gm = grid_for(g.nkeys);
     hipLaunchKernelGGL(k_mcc_small<T>, dim3(gm), dim3(kBlock), 0, c->stream, a);
-    hipLaunchKernelGGL(k_mcc_cells<T>, dim3(gm), dim3(kBlock), 0, c->stream, a);
+    e = scan_u32(c, c->mcc_count, c->mcc_count, (int64_t)gm * (kBlock / 64), nullptr, c->dyn + 8, false, false);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_mcc_compact<T>, dim3(gm), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(k_mcc_cells<T>, dim3(2048), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(k_mcc_big<T>, dim3(1024), dim3(64), 0, c->stream, a);
     toc(c, tm);
     hipLaunchKernelGGL(k_fi_resolve<T>, dim3(grid_for(c->buf.cap[2])), dim3(kBlock), 0, c->stream, a, c->fi_list,

@@ -99,13 +99,14 @@ size_t pic::scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[
     t->dyn = (uint32_t*)take(64 * sizeof(uint32_t));
     t->id_ptrs = (uint32_t**)take(3 * sizeof(uint32_t*));
     t->mom_out = (double*)take(16 * sizeof(double));
-    t->xs = (double*)take(3 * (size_t)cfg->xs_n * sizeof(double));
+    t->xs = (double*)take(5 * (size_t)cfg->xs_n * sizeof(double));  // el, iz, cx, rate bounds of the two classes
     t->off = (uint32_t*)take((nc + 1) * 4);
     for (int s = 0; s < 3; ++s) t->key[s] = (uint32_t*)take(cap[s] * 4);
     t->bins = (uint32_t*)take(capsum * 4);
     t->big = (uint32_t*)take(nc * 4);
     t->mcc_list = (uint32_t*)take(nc * 4);
     t->mcc_count = (uint32_t*)take(4 * 8192 * 4);
+    t->mcc_dense = (uint32_t*)take(nc * 4);
     t->fi_list = (uint32_t*)take(cap[2] * 4);
     t->push_part = (uint32_t*)take(8192 * 8 * 4);
     t->nflag = (uint32_t*)take(cap[2] * 4);
@@ -220,14 +221,31 @@ pic_status pic_init(const pic_config* cfg, const pic_buffers* bufs, void* hip_st
             c->fi_thr = lo;
         }
     }
-    double mel = 0, miz = 0, mcx = 0;
-    for (int k = 0; k < cfg->xs_n; ++k) {
-        mel = std::max(mel, cfg->xs_el[k]);
-        miz = std::max(miz, cfg->xs_iz[k]);
-        mcx = std::max(mcx, cfg->xs_cx[k]);
+    // Bounds of the collision rate u sigma_tot(E(u)) for the null-collision
+    // test, per pair class (0: e-Cu, el + iz; 1: Cu+-Cu, cx): entry k bounds
+    // every relative speed whose energy E = m u^2 / 2 is at most that of
+    // table node k + 1. The tables are linear in ln E between nodes and u
+    // grows with E, so on a segment u sigma is at most the segment's top
+    // speed times the larger of its two node values; below the first node
+    // sigma is the first value.
+    {
+        const int n = cfg->xs_n;
+        const double lnr = std::log(cfg->xs_emax / cfg->xs_emin);
+        c->nu_tab.assign(2 * (size_t)n, 0.0);
+        for (int cls = 0; cls < 2; ++cls) {
+            const double m = cls == 0 ? kMe : cfg->m_ion;
+            auto sig = [&](int k) { return cls == 0 ? cfg->xs_el[k] + cfg->xs_iz[k] : cfg->xs_cx[k]; };
+            auto speed = [&](int k) {
+                return std::sqrt(2.0 * cfg->xs_emin * std::exp(lnr * k / (n - 1)) * kQe / m);
+            };
+            double cum = speed(0) * sig(0);
+            for (int k = 0; k < n - 1; ++k) {
+                cum = std::max(cum, speed(k + 1) * std::max(sig(k), sig(k + 1)));
+                c->nu_tab[(size_t)cls * n + k] = cum;
+            }
+            c->nu_tab[(size_t)cls * n + n - 1] = cum;
+        }
     }
-    c->xs_max[0] = mel + miz;
-    c->xs_max[1] = mcx;
     c->npatch = 0;
     if (cfg->fn_rings > 0) c->npatch = ((int64_t)cfg->fn_rings + (int64_t)std::ceil(g.zc)) * cfg->fn_az;
 
@@ -245,6 +263,8 @@ pic_status pic_init(const pic_config* cfg, const pic_buffers* bufs, void* hip_st
     H(hipMemcpyAsync(c->xs, cfg->xs_el, cfg->xs_n * 8, hipMemcpyHostToDevice, c->stream), "copy tables");
     H(hipMemcpyAsync(c->xs + cfg->xs_n, cfg->xs_iz, cfg->xs_n * 8, hipMemcpyHostToDevice, c->stream), "copy tables");
     H(hipMemcpyAsync(c->xs + 2 * cfg->xs_n, cfg->xs_cx, cfg->xs_n * 8, hipMemcpyHostToDevice, c->stream),
+      "copy tables");
+    H(hipMemcpyAsync(c->xs + 3 * cfg->xs_n, c->nu_tab.data(), 2 * cfg->xs_n * 8, hipMemcpyHostToDevice, c->stream),
       "copy tables");
     uint32_t* ids[3] = {bufs->id[0], bufs->id[1], bufs->id[2]};
     H(hipMemcpyAsync(c->id_ptrs, ids, sizeof(ids), hipMemcpyHostToDevice, c->stream), "copy id pointers");

@@ -5,6 +5,7 @@
 // nodes i..i+1, j..j+1, k..k+1 and has index (k*(ny-1) + j)*(nx-1) + i.
 #pragma once
 
+#include <vector>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -351,7 +352,7 @@ struct pic_ctx {
     double V0 = 0.0, F1 = 0.0;
     double kq[3];                 // kick per step in grid units per V/m
     double adk_c = 0.0, adk_n = 0.0, fi_thr = 0.0, ebsi = 0.0;
-    double xs_max[2];             // max total cross section per pair class [m^2]
+    std::vector<double> nu_tab;   // host copy of the collision-rate bounds (2 x xs_n), uploaded after the tables
     int64_t npatch = 0;
     int64_t id_cap = 0, bm_words = 0;
     // scratch carve
@@ -363,6 +364,7 @@ struct pic_ctx {
     uint32_t* big = nullptr;      // big-cell list (nkeys)
     uint32_t* mcc_list = nullptr;   // small cells for the full collision pass (nkeys)
     uint32_t* mcc_count = nullptr;  // cells per scanning wavefront (4 x 8192)
+    uint32_t* mcc_dense = nullptr;  // the listed cells, compacted (nkeys)
     uint32_t* fi_list = nullptr;  // cap neutral
     uint32_t* push_part = nullptr;  // per-block partials of the push kernels (8192 x 8)
     uint32_t* nflag = nullptr;    // cap neutral: step+1 if the neutral had an event
