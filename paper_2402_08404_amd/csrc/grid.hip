@@ -326,6 +326,82 @@ __global__ __launch_bounds__(kResidBlock) void k_cg_resid(CgArgs a) {
     if (threadIdx.x == 0) a.part_rr[blockIdx.x] = tr;
 }
 
+// The same residual as a z-marching kernel (see ZMarch): the values and
+// node types of the planes below and above come from registers, the
+// in-plane neighbours from L1/L2. At most kCgBlocks blocks; block 0 clears
+// the partial slots of the blocks that do not exist, so the consumers sum
+// kCgBlocks partials as for k_cg_resid.
+__global__ __launch_bounds__(kBlock) void k_cg_resid_z(CgArgs a, int kc) {
+    const Grid& g = a.g;
+    const ZMarch t = zmarch(g.nx, g.ny, g.nz, kc);
+    const int64_t pl = (int64_t)g.nx * g.ny;
+    double bb = 0.0, rr = 0.0;
+    if (t.col) {
+        const int i = t.i, j = t.j;
+        const double hx = half_at_edge(i, g.nx), hy = half_at_edge(j, g.ny);
+        // neighbours outside the grid are read at the node itself with weight
+        // zero, so every load is unconditional
+        const int64_t ow = i > 0 ? -1 : 0, oe = i < g.nx - 1 ? 1 : 0;
+        const int64_t os = j > 0 ? -(int64_t)g.nx : 0, on = j < g.ny - 1 ? (int64_t)g.nx : 0;
+        int64_t n = (int64_t)t.k0 * pl + (int64_t)j * g.nx + i;
+        double xm = a.x[t.k0 > 0 ? n - pl : n], xc = a.x[n];
+        uint8_t tm = a.type[t.k0 > 0 ? n - pl : n], tc = a.type[n];
+        for (int k = t.k0; k < t.k1; ++k, n += pl) {
+            const bool up = k + 1 < g.nz;
+            const double xp = a.x[up ? n + pl : n];
+            const uint8_t tp = a.type[up ? n + pl : n];
+            const double xw = a.x[n + ow], xe = a.x[n + oe], xs = a.x[n + os], xn = a.x[n + on];
+            const uint8_t tw = a.type[n + ow], te = a.type[n + oe], ts = a.type[n + os], tn = a.type[n + on];
+            const double qv = (double)a.rho[n] * a.qscale;
+            ((double*)a.p_old)[n] = 0.0;
+            const double hz = half_at_edge(k, g.nz);
+            const double fx = hy * hz, fy = hx * hz, fz = hx * hy;
+            const double xj[6] = {xw, xe, xs, xn, xm, xp};
+            const uint8_t tj[6] = {tw, te, ts, tn, tm, tp};
+            const double w[6] = {i > 0 ? fx : 0.0, i < g.nx - 1 ? fx : 0.0, j > 0 ? fy : 0.0,
+                                 j < g.ny - 1 ? fy : 0.0, k > 0 ? fz : 0.0, up ? fz : 0.0};
+            double lx = 0.0, bv = qv;
+#pragma unroll
+            for (int q = 0; q < 6; ++q) {
+                lx += w[q] * (xc - xj[q]);
+                bv += (tj[q] != 0 ? w[q] : 0.0) * xj[q];
+            }
+            const double rv = qv - lx;
+            if (tc == 0) {
+                a.r[n] = rv;
+                bb += bv * bv;
+                rr += rv * rv;
+            }
+            xm = xc;
+            xc = xp;
+            tm = tc;
+            tc = tp;
+        }
+    }
+    __shared__ double sh[kBlock / 64];
+    const double tb = block_sum(bb, sh);
+    if (threadIdx.x == 0) a.part_bb[blockIdx.x] = tb;
+    const double tr = block_sum(rr, sh);
+    if (threadIdx.x == 0) a.part_rr[blockIdx.x] = tr;
+    if (blockIdx.x == 0)
+        for (int b = (int)gridDim.x + (int)threadIdx.x; b < kCgBlocks; b += kBlock) a.part_bb[b] = a.part_rr[b] = 0.0;
+}
+
+// Initial residual and its partials: the z-marching kernel where the grid
+// fits in kCgBlocks blocks, else k_cg_resid.
+static void launch_resid(pic_ctx* c, const CgArgs& a) {
+    const Grid& g = a.g;
+    const int64_t cols = (int64_t)((g.nx + 63) / 64) * ((g.ny + 3) / 4);
+    if (cols <= kCgBlocks) {
+        int64_t kc = (g.nz * cols + kCgBlocks - 1) / kCgBlocks;
+        while (cols * ((g.nz + kc - 1) / kc) > kCgBlocks) ++kc;
+        const unsigned zb = (unsigned)(cols * ((g.nz + kc - 1) / kc));
+        hipLaunchKernelGGL(k_cg_resid_z, dim3(zb), dim3(kBlock), 0, c->stream, a, (int)kc);
+    } else {
+        hipLaunchKernelGGL(k_cg_resid, dim3(kCgBlocks), dim3(kResidBlock), 0, c->stream, a);
+    }
+}
+
 // Iteration it: finish r.r of the previous iteration (or of the initial
 // residual), test convergence, then p_new = r + beta p_old, q = A p_new and
 // the partials of p_new . q.
@@ -449,7 +525,7 @@ int cg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess, 
     a.chunk = ((g.nn + kCgBlocks - 1) / kCgBlocks + kBlock - 1) / kBlock * kBlock;
     hipLaunchKernelGGL(k_cg_setup, dim3(1), dim3(1), 0, c->stream, c->st, rtol, maxit);
     hipLaunchKernelGGL(k_cg_init, dim3((unsigned)G), dim3(kBlock), 0, c->stream, a, guess == PIC_GUESS_ZERO);
-    hipLaunchKernelGGL(k_cg_resid, dim3(kCgBlocks), dim3(kResidBlock), 0, c->stream, a);
+    launch_resid(c, a);
     double* pa = c->cg_p0;
     double* pb = c->cg_p1;
     int chunk = 8;
@@ -812,7 +888,7 @@ int mgcg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess
     a.chunk = ((g.nn + kCgBlocks - 1) / kCgBlocks + kBlock - 1) / kBlock * kBlock;
     hipLaunchKernelGGL(k_cg_setup, dim3(1), dim3(1), 0, c->stream, c->st, rtol, maxit);
     hipLaunchKernelGGL(k_cg_init, dim3((unsigned)G), dim3(kBlock), 0, c->stream, a, guess == PIC_GUESS_ZERO);
-    hipLaunchKernelGGL(k_cg_resid, dim3(kCgBlocks), dim3(kResidBlock), 0, c->stream, a);
+    launch_resid(c, a);
     int e = pcg_iterate<double>(c, phi, c->cg_r, c->cg_p0, c->cg_p1, c->cg_q, maxit, 0);
     if (e) return e;
     hipLaunchKernelGGL(k_cg_zero_free, dim3((unsigned)G), dim3(kBlock), 0, c->stream, g, c->buf.node_type, phi,
@@ -909,7 +985,7 @@ int mixed_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int gues
     double bn = 0.0, rn = 0.0, rn0 = -1.0;
     bool conv = false;
     for (int outer = 0; outer < 40; ++outer) {
-        hipLaunchKernelGGL(k_cg_resid, dim3(kCgBlocks), dim3(kResidBlock), 0, c->stream, a);
+        launch_resid(c, a);
         hipLaunchKernelGGL(k_mix_test, dim3(1), dim3(kBlock), 0, c->stream, (const double*)a.part_rr,
                            (const double*)a.part_bb, c->st);
         (void)hipMemcpyAsync(c->host_st, c->st, sizeof(DevState), hipMemcpyDeviceToHost, c->stream);
