@@ -899,13 +899,23 @@ __global__ __launch_bounds__(kBlock) void k_mg_fine_sweep(MgArgs a, const TB* __
         double vm = in(t.k0 > 0 ? n - pl : n, cw);
         if (t.k0 == 0) vm = 0.0;
         double vc = in(n, cw);
+        // kFineFirst: b of the node, carried from the previous step's load of
+        // the plane above (a load of b0[n] of its own came after the waits
+        // for the neighbours, a second memory latency per step)
+        double bc = MODE == kFineFirst ? (double)b0[n] : 0.0;
         for (int k = t.k0; k < t.k1; ++k, n += pl) {
             const bool up = k + 1 < g.nz;
-            double vp = in(up ? n + pl : n, cw);
-            if (!up) vp = 0.0;
+            double bp = 0.0, vp;
+            if (MODE == kFineFirst) {
+                bp = (double)b0[up ? n + pl : n];
+                vp = up ? cw * bp : 0.0;
+            } else {
+                vp = in(up ? n + pl : n, cw);
+                if (!up) vp = 0.0;
+            }
             const double xw = in(n + ow, cwW), xe = in(n + oe, cwE);
             const double xs = in(n + os, cwS), xn = in(n + on, cwN);
-            const double bn = (double)b0[n];
+            const double bn = MODE == kFineFirst ? bc : (double)b0[n];
             const bool fr = a.type[n] == 0;
             // a free node is never on a z face: fx = hy, fy = hx (hz = 1)
             double acc = 0.0;
@@ -921,6 +931,7 @@ __global__ __launch_bounds__(kBlock) void k_mg_fine_sweep(MgArgs a, const TB* __
             xo[n] = out;
             vm = vc;
             vc = vp;
+            bc = bp;
         }
     }
     if (LAST) {
