@@ -122,24 +122,49 @@ __global__ void k_scan_reduce(const uint32_t* __restrict__ in, int64_t n, const 
 
 // Exclusive scan of the tile sums in one block (any count); writes the total.
 __global__ void k_scan_top(uint32_t* bsum, int64_t nb, uint32_t* total) {
-    __shared__ uint32_t sh[kBlock];
+    // chunks of kBlock x 8 block sums: each thread scans 8 consecutive
+    // values (loaded together: the index is clamped, the value masked), the
+    // threads' totals are scanned by wavefront shuffles and the four
+    // wavefront totals through LDS
+    constexpr int kPer = 8;
+    __shared__ uint32_t wsum[kBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint32_t carry = 0;
-    for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
-        int64_t i = b0 + threadIdx.x;
-        uint32_t v = i < nb ? bsum[i] : 0u;
-        sh[threadIdx.x] = v;
-        __syncthreads();
-        for (int o = 1; o < kBlock; o <<= 1) {
-            uint32_t add = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0u;
-            __syncthreads();
-            sh[threadIdx.x] += add;
-            __syncthreads();
+    for (int64_t b0 = 0; b0 < nb; b0 += (int64_t)kBlock * kPer) {
+        const int64_t base = b0 + (int64_t)threadIdx.x * kPer;
+        uint32_t v[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int64_t idx = base + q < nb ? base + q : nb - 1;
+            const uint32_t x = bsum[idx];
+            v[q] = base + q < nb ? x : 0u;
         }
-        uint32_t incl = sh[threadIdx.x];
-        if (i < nb) bsum[i] = carry + incl - v;
-        uint32_t last = sh[kBlock - 1];
+        uint32_t s = 0;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) s += v[q];
+        uint32_t x = s;  // inclusive scan of the threads' totals in the wavefront
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
         __syncthreads();
-        carry += last;
+        uint32_t wpre = 0, tot = 0;
+#pragma unroll
+        for (int q = 0; q < kBlock / 64; ++q) {
+            const uint32_t t = wsum[q];
+            wpre += q < w ? t : 0u;
+            tot += t;
+        }
+        uint32_t run = carry + wpre + x - s;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            if (base + q < nb) bsum[base + q] = run;
+            run += v[q];
+        }
+        carry += tot;
+        __syncthreads();  // wsum is rewritten by the next chunk
     }
     if (threadIdx.x == 0 && total) *total = carry;
 }
