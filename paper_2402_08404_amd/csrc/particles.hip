@@ -180,17 +180,37 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs<T> a) {
     }
 }
 
-// Reduction of the push partials of one species (one block, block order).
+// Reduction of the push partials of one species (one block of 1024
+// threads; each thread loads up to 8 blocks' entries together: integer sums
+// and a maximum, so the order does not matter).
+constexpr int kFinalBlock = 1024;
+
 template <int SP>
-__global__ void k_push_final(DevState* st, const uint32_t* part, int nblocks) {
-    __shared__ unsigned long long sh[kBlock / 64];
-    __shared__ unsigned int shm[kBlock / 64];
+__global__ __launch_bounds__(kFinalBlock) void k_push_final(DevState* st, const uint32_t* part, int nblocks) {
+    __shared__ unsigned long long sh[kFinalBlock / 64];
+    __shared__ unsigned int shm[kFinalBlock / 64];
     unsigned int m = 0;
     unsigned long long s[6] = {0, 0, 0, 0, 0, 0};
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
-        const uint32_t* q = part + (int64_t)b * 8;
-        m = q[0] > m ? q[0] : m;
-        for (int k = 1; k < 6; ++k) s[k] += q[k];
+    for (int b0 = 0; b0 < nblocks; b0 += 8 * kFinalBlock) {
+        uint4 lo[8];
+        uint2 hi[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int b = b0 + u * kFinalBlock + (int)threadIdx.x;
+            const uint32_t* q = part + (int64_t)(b < nblocks ? b : 0) * 8;
+            lo[u] = *(const uint4*)q;
+            hi[u] = *(const uint2*)(q + 4);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (b0 + u * kFinalBlock + (int)threadIdx.x >= nblocks) continue;
+            m = lo[u].x > m ? lo[u].x : m;
+            s[1] += lo[u].y;
+            s[2] += lo[u].z;
+            s[3] += lo[u].w;
+            s[4] += hi[u].x;
+            s[5] += hi[u].y;
+        }
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
@@ -1158,11 +1178,11 @@ static hipError_t particles_t(pic_ctx* c, bool move) {
             if (s == 2) hipLaunchKernelGGL((k_push<T, 2, false>), dim3(G), dim3(kBlock), 0, c->stream, a);
         }
         toc(c, t_e);
-        if (s == 0) hipLaunchKernelGGL(k_push_final<0>, dim3(1), dim3(kBlock), 0, c->stream, c->st,
+        if (s == 0) hipLaunchKernelGGL(k_push_final<0>, dim3(1), dim3(kFinalBlock), 0, c->stream, c->st,
                                        (const uint32_t*)a.part, (int)G);
-        if (s == 1) hipLaunchKernelGGL(k_push_final<1>, dim3(1), dim3(kBlock), 0, c->stream, c->st,
+        if (s == 1) hipLaunchKernelGGL(k_push_final<1>, dim3(1), dim3(kFinalBlock), 0, c->stream, c->st,
                                        (const uint32_t*)a.part, (int)G);
-        if (s == 2) hipLaunchKernelGGL(k_push_final<2>, dim3(1), dim3(kBlock), 0, c->stream, c->st,
+        if (s == 2) hipLaunchKernelGGL(k_push_final<2>, dim3(1), dim3(kFinalBlock), 0, c->stream, c->st,
                                        (const uint32_t*)a.part, (int)G);
         if (s == 2) toc(c, c->push_all_handle);
         if (s == 0) c->push_all_handle = t_all;
