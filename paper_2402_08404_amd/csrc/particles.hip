@@ -1,6 +1,8 @@
 // particles.hip -- particle kernels of one PIC-MCC step: push with deposit and
 // binning, cell bins, Monte Carlo collisions, field ionization, products,
 // reordering by cell, field emission, explicit loads.
+#include <algorithm>
+
 #include "pic_internal.hpp"
 
 namespace pic {
@@ -1235,12 +1237,15 @@ static hipError_t collide_t(pic_ctx* c, bool record) {
     int tm = tic(c, PIC_T_MCC);
     // the scan and the compaction take the same grid (a wavefront of the
     // second copies the segment of the same wavefront of the first)
-    const unsigned gm = grid_for(g.nkeys);
+    // on the side stream (concurrent with the Poisson solve) the collision
+    // kernels take a part of the GPU only, so the solve keeps most of it
+    const bool side = c->stream == c->side_stream;
+    const unsigned gm = side ? std::min(grid_for(g.nkeys), 1024u) : grid_for(g.nkeys);
     hipLaunchKernelGGL(k_mcc_small<T>, dim3(gm), dim3(kBlock), 0, c->stream, a);
     e = scan_u32(c, c->mcc_count, c->mcc_count, (int64_t)gm * (kBlock / 64), nullptr, c->dyn + 8, false, false);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_mcc_compact<T>, dim3(gm), dim3(kBlock), 0, c->stream, a);
-    hipLaunchKernelGGL(k_mcc_cells<T>, dim3(2048), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(k_mcc_cells<T>, dim3(side ? 256 : 2048), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(k_mcc_big<T>, dim3(1024), dim3(64), 0, c->stream, a);
     toc(c, tm);
     hipLaunchKernelGGL(k_fi_resolve<T>, dim3(grid_for(c->buf.cap[2])), dim3(kBlock), 0, c->stream, a, c->fi_list,

@@ -384,6 +384,15 @@ static pic_status solve(pic_ctx* c, int solver, int guess, double rtol, int maxi
     return PIC_OK;
 }
 
+// The side stream (default priority) and its two events, created on first use.
+static hipError_t side_init(pic_ctx* c) {
+    if (c->side_stream) return hipSuccess;
+    hipError_t e = hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_dep, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&c->ev_col, hipEventDisableTiming);
+    return e;
+}
+
 pic_status pic_step(pic_ctx* c, int32_t nsteps, uint32_t flags) {
     if (!c) return PIC_E_INVALID_ARG;
     if (c->failed) return PIC_E_STATE;
@@ -403,20 +412,39 @@ pic_status pic_step(pic_ctx* c, int32_t nsteps, uint32_t flags) {
             s = hip_check(c, particles_phase(c, (flags & PIC_STEP_PUSH) != 0), "push");
             toc(c, t);
         }
+        // The collisions touch only the particles and their bins, the solve
+        // only the charge (already deposited), the potential and the field,
+        // so without profiling a step that does both runs its collisions on
+        // the side stream, concurrently with the solve.
+        const bool side = !c->prof && (flags & PIC_STEP_COLLIDE) && (flags & PIC_STEP_SOLVE);
+        bool joined = true;
         if (s == PIC_OK && (flags & PIC_STEP_COLLIDE)) {
             if (!c->bins_valid) return fail(c, PIC_E_INVALID_ARG, "the collide phase needs a push or deposit phase first");
-            int t = tic(c, PIC_T_COLLIDE);
-            s = hip_check(c, collide_phase(c, (flags & PIC_STEP_EVENTS) != 0), "collide");
-            toc(c, t);
+            if (side) {
+                s = hip_check(c, side_init(c), "side stream");
+                if (s != PIC_OK) return s;
+                s = hip_check(c, hipEventRecord(c->ev_dep, c->stream), "event");
+                if (s == PIC_OK) s = hip_check(c, hipStreamWaitEvent(c->side_stream, c->ev_dep, 0), "event");
+                if (s != PIC_OK) return s;
+                hipStream_t keep = c->stream;
+                c->stream = c->side_stream;
+                hipError_t e = collide_phase(c, (flags & PIC_STEP_EVENTS) != 0);
+                if (e == hipSuccess) e = hipEventRecord(c->ev_col, c->side_stream);
+                c->stream = keep;
+                s = hip_check(c, e, "collide");
+                joined = false;
+            } else {
+                int t = tic(c, PIC_T_COLLIDE);
+                s = hip_check(c, collide_phase(c, (flags & PIC_STEP_EVENTS) != 0), "collide");
+                toc(c, t);
+            }
         }
         if (s == PIC_OK && (flags & PIC_STEP_SOLVE)) {
             // guess: the previous potential, or phi_n + (phi_n - phi_{n-1})
             // once two step solves are on record (phi_prev keeps phi_n)
-            if (c->cfg.step_guess == 1) {
-                s = hip_check(c, extrapolate_phi(c, c->phi_hist >= 2), "extrapolation");
-                if (s != PIC_OK) return s;
-            }
-            s = solve(c, c->cfg.solver, PIC_GUESS_PREVIOUS, c->cfg.step_rtol, c->cfg.step_maxit, nullptr);
+            if (c->cfg.step_guess == 1) s = hip_check(c, extrapolate_phi(c, c->phi_hist >= 2), "extrapolation");
+            if (s == PIC_OK)
+                s = solve(c, c->cfg.solver, PIC_GUESS_PREVIOUS, c->cfg.step_rtol, c->cfg.step_maxit, nullptr);
             if (s == PIC_E_NOT_CONVERGED) {
                 result = s;
                 s = PIC_OK;
@@ -426,6 +454,11 @@ pic_status pic_step(pic_ctx* c, int32_t nsteps, uint32_t flags) {
             }
         } else if (s == PIC_OK && (flags & PIC_STEP_FIELD)) {
             s = hip_check(c, launch_field(c, c->buf.phi, c->buf.field), "field");
+        }
+        // everything after this step on the library stream follows its collisions
+        if (!joined) {
+            pic_status sj = hip_check(c, hipStreamWaitEvent(c->stream, c->ev_col, 0), "event");
+            if (s == PIC_OK) s = sj;
         }
         toc(c, th);
         if (s != PIC_OK) return s;
@@ -518,6 +551,12 @@ void pic_destroy(pic_ctx* c) {
     if (c->mix_exec) (void)hipGraphExecDestroy(c->mix_exec);
     if (c->mix_graph) (void)hipGraphDestroy(c->mix_graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    if (c->side_stream) {
+        (void)hipStreamSynchronize(c->side_stream);
+        (void)hipStreamDestroy(c->side_stream);
+    }
+    if (c->ev_dep) (void)hipEventDestroy(c->ev_dep);
+    if (c->ev_col) (void)hipEventDestroy(c->ev_col);
     mg_free(c);
     delete c;
 }

@@ -394,6 +394,11 @@ struct pic_ctx {
     // captured pair of preconditioned CG iterations (built at the first
     // unprofiled multigrid solve)
     hipStream_t cap_stream = nullptr;
+    // a step's collisions run on side_stream, concurrently with its Poisson
+    // solve (which needs only the deposit): ev_dep orders them after the
+    // deposit, ev_col orders the rest of the step after them
+    hipStream_t side_stream = nullptr;
+    hipEvent_t ev_dep = nullptr, ev_col = nullptr;
     hipGraph_t pcg_graph = nullptr, mix_graph = nullptr;
     hipGraphExec_t pcg_exec = nullptr, mix_exec = nullptr;
     int last_iters[3] = {0, 0, 0};   // iterations of the last solve per solver (first launch chunk)
