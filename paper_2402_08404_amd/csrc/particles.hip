@@ -1311,7 +1311,7 @@ hipError_t collide_phase(pic_ctx* c, bool record) {
 // field one spacing out along the normal gives the Murphy-Good current
 // density J; N = J A dt / e electrons are expected, floor(N) are injected
 // plus one with probability frac(N), uniformly on the patch, 10^-3 spacings
-// outside the surface, at rest. Ids follow patch order. One block does it all.
+// outside the surface, at rest. Ids follow patch order.
 
 struct InjArgs {
     Grid g;
@@ -1323,6 +1323,9 @@ struct InjArgs {
     uint32_t step;
     DevState* st;
     int64_t cap;
+    double phi_w15;    // phi_w^1.5, taken on the host
+    uint32_t* cnt;     // count of each patch
+    double* part;      // per count block: expected count, clamped patches
 };
 
 __device__ inline double interp_phi(const Grid& g, const double* phi, double X, double Y, double Z) {
@@ -1384,7 +1387,7 @@ __device__ inline int64_t patch_count(const InjArgs& a, int64_t p, double* nexp,
         double lf = log(f);
         double v = 1.0 - f + (f / 6.0) * lf;
         double t = 1.0 + f / 9.0 - (f / 18.0) * lf;
-        J = a.fn_a * F * F / (a.phi_w * t * t) * exp(-v * a.fn_b * pow(a.phi_w, 1.5) / F);
+        J = a.fn_a * F * F / (a.phi_w * t * t) * exp(-v * a.fn_b * a.phi_w15 / F);
     }
     double N = J * q[6] * a.h * a.h * a.dt / kQe;
     *nexp = N;
@@ -1393,79 +1396,145 @@ __device__ inline int64_t patch_count(const InjArgs& a, int64_t p, double* nexp,
     return (int64_t)fl + ((u.a < N - fl) ? 1 : 0);
 }
 
-template <typename T>
-__global__ __launch_bounds__(1024) void k_inject(InjArgs a, Species<T> e) {
-    __shared__ int64_t sh[1024];
-    __shared__ double shd[16];
-    __shared__ int64_t total_sh;
-    const int B = blockDim.x;
-    // pass 1: totals
-    int64_t tot = 0, ncl = 0;
-    double nexp_acc = 0.0;
-    for (int64_t r0 = 0; r0 < a.npatch; r0 += B) {
-        int64_t p = r0 + threadIdx.x;
-        double ne = 0.0;
-        int cl = 0;
-        int64_t k = p < a.npatch ? patch_count(a, p, &ne, &cl) : 0;
-        tot += k;
-        ncl += cl;
-        double s = block_sum(ne, shd);
-        if (threadIdx.x == 0) nexp_acc += s;
+// Counts of every patch, one patch per thread over many blocks (the work is
+// FP64 transcendentals and a gather, too much for one compute unit). A count
+// that does not fit 32 bits is stored as 0xffffffff, which overflows any
+// buffer. Each block leaves its sums of the expected counts and of the
+// clamped patches, added later in block order.
+__global__ __launch_bounds__(kInjCountBlock) void k_inject_count(InjArgs a) {
+    __shared__ double shd[kInjCountBlock / 64];
+    const int64_t p = (int64_t)blockIdx.x * kInjCountBlock + threadIdx.x;
+    double ne = 0.0;
+    int cl = 0;
+    if (p < a.npatch) {
+        const int64_t k = patch_count(a, p, &ne, &cl);
+        a.cnt[p] = (uint32_t)min(k, (int64_t)0xffffffffLL);
     }
-    __shared__ int64_t shi[16];
-    int64_t T1 = block_sum(tot, shi);
-    int64_t C1 = block_sum(ncl, shi);
+    const double NE = block_sum(ne, shd);
+    const double CL = block_sum((double)cl, shd);
     if (threadIdx.x == 0) {
-        total_sh = T1;
-        a.st->fn_expected += nexp_acc;
-        a.st->fn_clamped += (unsigned long long)C1;
+        a.part[2 * blockIdx.x] = NE;
+        a.part[2 * blockIdx.x + 1] = CL;
     }
+}
+
+// Electrons of the emission, in patch order: one block of 1024 threads over
+// chunks of 8192 patches. The chunk's counts go to shared memory and a block
+// scan turns them into offsets in patch order (each thread takes a run of 8,
+// wavefront shuffles, then the 16 wavefront totals); then the chunk's
+// electrons are spread evenly over the threads, each finding its patch by
+// binary search over the offsets, so that consecutive electrons go to
+// consecutive slots. A chunk that would overflow the buffer sets the capacity
+// error; its electrons and those of later chunks are not made, and the
+// particle count is left as it was. The expected count takes every patch.
+constexpr int kInjBlock = 1024, kInjPer = 8, kInjChunk = kInjBlock * kInjPer;
+
+// exclusive prefix of v over the block and the block total
+__device__ inline int64_t inj_scan(int64_t v, int64_t* wsum, int64_t& total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = __shfl_up(x, o);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
     __syncthreads();
-    int64_t total = total_sh;
-    int64_t base = (int64_t)a.st->n_slots[PIC_ELECTRON];
-    uint32_t id0 = (uint32_t)a.st->next_id;
-    if (total == 0) return;
-    if (base + total > a.cap) {
-        if (threadIdx.x == 0) atomicCAS(&a.st->error, 0, PIC_E_CAPACITY);
-        return;
+    int64_t pre = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < kInjBlock / 64; ++q) {
+        const int64_t t = wsum[q];
+        pre += q < w ? t : 0;
+        tot += t;
     }
-    // pass 2: offsets in patch order and the electrons
+    __syncthreads();  // wsum is reused by the next call
+    total = tot;
+    return pre + x - v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kInjBlock) void k_inject(InjArgs a, Species<T> e) {
+    __shared__ uint32_t poff[kInjChunk];  // counts, then offsets within the chunk
+    __shared__ int64_t wsum[kInjBlock / 64];
+    __shared__ double shd[kInjBlock / 64];
+    const int t = threadIdx.x;
+    const int64_t base = (int64_t)a.st->n_slots[PIC_ELECTRON];
+    const uint32_t id0 = (uint32_t)a.st->next_id;
     int64_t carry = 0;
-    for (int64_t r0 = 0; r0 < a.npatch; r0 += B) {
-        int64_t p = r0 + threadIdx.x;
-        double ne;
-        int cl;
-        int64_t k = p < a.npatch ? patch_count(a, p, &ne, &cl) : 0;
-        sh[threadIdx.x] = k;
-        __syncthreads();
-        for (int o = 1; o < B; o <<= 1) {
-            int64_t add = threadIdx.x >= (unsigned)o ? sh[threadIdx.x - o] : 0;
-            __syncthreads();
-            sh[threadIdx.x] += add;
-            __syncthreads();
+    bool over = false;
+    for (int64_t c0 = 0; c0 < a.npatch; c0 += kInjChunk) {
+        bool big = false;
+#pragma unroll
+        for (int u = 0; u < kInjPer; ++u) {
+            const int64_t p = c0 + u * kInjBlock + t;
+            const uint32_t k = p < a.npatch ? a.cnt[p] : 0u;
+            big |= k == 0xffffffffu;
+            poff[u * kInjBlock + t] = k;
         }
-        int64_t off = carry + sh[threadIdx.x] - k;
-        for (int64_t j = 0; j < k; ++j) {
-            Draw2 u = draw2(a.seed, (uint32_t)p, a.step, kTagInj, (uint32_t)(1 + j));
-            double q[7];
-            patch_point(a, p, u.a, u.b, q);
-            int64_t m = base + off + j;
-            e.x[m] = (T)(q[0] + 1e-3 * q[3]);
-            e.y[m] = (T)(q[1] + 1e-3 * q[4]);
-            e.z[m] = (T)(q[2] + 1e-3 * q[5]);
-            e.vx[m] = (T)0;
-            e.vy[m] = (T)0;
-            e.vz[m] = (T)0;
-            e.id[m] = id0 + (uint32_t)(off + j);
+        big = __syncthreads_or(big);
+        // offsets in patch order
+        uint32_t r[kInjPer];
+        int64_t run = 0;
+#pragma unroll
+        for (int u = 0; u < kInjPer; ++u) {
+            r[u] = poff[t * kInjPer + u];
+            run += r[u];
         }
-        int64_t last = sh[B - 1];
+        int64_t tchunk;
+        int64_t o = inj_scan(run, wsum, tchunk);
+        over = over || big || base + carry + tchunk > a.cap || tchunk > (int64_t)0xffffffffLL;
+        if (!over) {
+#pragma unroll
+            for (int u = 0; u < kInjPer; ++u) {
+                poff[t * kInjPer + u] = (uint32_t)o;
+                o += r[u];
+            }
+        }
         __syncthreads();
-        carry += last;
+        if (!over) {
+            for (int64_t q = t; q < tchunk; q += kInjBlock) {
+                // the last patch whose offset is <= q (offsets past the chunk's
+                // last patch equal the chunk total, which is > q)
+                int lo = 0;
+#pragma unroll
+                for (int s = kInjChunk / 2; s > 0; s >>= 1)
+                    if ((int64_t)poff[lo + s] <= q) lo += s;
+                const int64_t p = c0 + lo, j = q - (int64_t)poff[lo];
+                Draw2 d = draw2(a.seed, (uint32_t)p, a.step, kTagInj, (uint32_t)(1 + j));
+                double pt[7];
+                patch_point(a, p, d.a, d.b, pt);
+                const int64_t m = base + carry + q;
+                e.x[m] = (T)(pt[0] + 1e-3 * pt[3]);
+                e.y[m] = (T)(pt[1] + 1e-3 * pt[4]);
+                e.z[m] = (T)(pt[2] + 1e-3 * pt[5]);
+                e.vx[m] = (T)0;
+                e.vy[m] = (T)0;
+                e.vz[m] = (T)0;
+                e.id[m] = id0 + (uint32_t)(carry + q);
+            }
+        }
+        carry += tchunk;
+        __syncthreads();  // poff is rewritten by the next chunk
     }
-    if (threadIdx.x == 0) {
-        a.st->n_slots[PIC_ELECTRON] += (unsigned long long)total;
-        a.st->next_id += (unsigned long long)total;
-        a.st->injected += (unsigned long long)total;
+    // the count blocks' sums, in block order
+    const int64_t nb = (a.npatch + kInjCountBlock - 1) / kInjCountBlock;
+    double ne = 0.0, cl = 0.0;
+    for (int64_t b = t; b < nb; b += kInjBlock) {
+        ne += a.part[2 * b];
+        cl += a.part[2 * b + 1];
+    }
+    const double NE = block_sum(ne, shd);
+    const double CL = block_sum(cl, shd);
+    if (t == 0) {
+        a.st->fn_expected += NE;
+        a.st->fn_clamped += (unsigned long long)CL;
+        if (over) {
+            atomicCAS(&a.st->error, 0, PIC_E_CAPACITY);
+        } else {
+            a.st->n_slots[PIC_ELECTRON] += (unsigned long long)carry;
+            a.st->next_id += (unsigned long long)carry;
+            a.st->injected += (unsigned long long)carry;
+        }
     }
 }
 
@@ -1486,11 +1555,16 @@ hipError_t inject_phase(pic_ctx* c) {
     a.step = (uint32_t)c->step;
     a.st = c->st;
     a.cap = c->buf.cap[0];
+    a.phi_w15 = pow(a.phi_w, 1.5);
+    a.cnt = c->inj_cnt;
+    a.part = c->inj_part;
     if (c->npatch == 0) return hipSuccess;
+    const int64_t nb = (c->npatch + kInjCountBlock - 1) / kInjCountBlock;
+    hipLaunchKernelGGL(k_inject_count, dim3((unsigned)nb), dim3(kInjCountBlock), 0, c->stream, a);
     if (c->cfg.precision == PIC_F32)
-        hipLaunchKernelGGL(k_inject<float>, dim3(1), dim3(1024), 0, c->stream, a, species<float>(c, 0));
+        hipLaunchKernelGGL(k_inject<float>, dim3(1), dim3(kInjBlock), 0, c->stream, a, species<float>(c, 0));
     else
-        hipLaunchKernelGGL(k_inject<double>, dim3(1), dim3(1024), 0, c->stream, a, species<double>(c, 0));
+        hipLaunchKernelGGL(k_inject<double>, dim3(1), dim3(kInjBlock), 0, c->stream, a, species<double>(c, 0));
     return hipGetLastError();
 }
 

@@ -109,6 +109,9 @@ size_t pic::scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[
     t->mcc_dense = (uint32_t*)take(nc * 4);
     t->fi_list = (uint32_t*)take(cap[2] * 4);
     t->push_part = (uint32_t*)take(8192 * 8 * 4);
+    const int64_t npatch = fn_patches(cfg);
+    t->inj_cnt = (uint32_t*)take(std::max<int64_t>(npatch, 1) * 4);
+    t->inj_part = (double*)take(2 * std::max<int64_t>((npatch + kInjCountBlock - 1) / kInjCountBlock, 1) * 8);
     t->nflag = (uint32_t*)take(cap[2] * 4);
     t->prod_list = (uint32_t*)take(cap[2] * 4);
     t->prod_ev = (int32_t*)take(cap[2] * 4);
@@ -246,8 +249,7 @@ pic_status pic_init(const pic_config* cfg, const pic_buffers* bufs, void* hip_st
             c->nu_tab[(size_t)cls * n + n - 1] = cum;
         }
     }
-    c->npatch = 0;
-    if (cfg->fn_rings > 0) c->npatch = ((int64_t)cfg->fn_rings + (int64_t)std::ceil(g.zc)) * cfg->fn_az;
+    c->npatch = fn_patches(cfg);
 
     pic_status st = PIC_OK;
     auto H = [&](hipError_t e, const char* w) {

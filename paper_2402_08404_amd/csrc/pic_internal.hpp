@@ -8,6 +8,7 @@
 #include <vector>
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <string>
 
@@ -342,6 +343,16 @@ __device__ inline double sum_partials_n(const double* __restrict__ part, int npa
 
 }  // namespace pic
 
+// Emission patches: fn_rings rings on the spherical cap, then one ring per
+// spacing of the cylinder's height, each ring cut into fn_az sectors; the
+// counts are taken by blocks of kInjCountBlock patches.
+constexpr int kInjCountBlock = 256;
+inline int64_t fn_patches(const pic_config* cfg) {
+    if (cfg->fn_rings <= 0) return 0;
+    const double zc = cfg->tip_h / cfg->h - cfg->tip_r / cfg->h;
+    return ((int64_t)cfg->fn_rings + (int64_t)std::ceil(zc)) * cfg->fn_az;
+}
+
 // ---------------------------------------------------------------------------
 // The context (host side).
 struct pic_ctx {
@@ -367,6 +378,8 @@ struct pic_ctx {
     uint32_t* mcc_dense = nullptr;  // the listed cells, compacted (nkeys)
     uint32_t* fi_list = nullptr;  // cap neutral
     uint32_t* push_part = nullptr;  // per-block partials of the push kernels (8192 x 8)
+    uint32_t* inj_cnt = nullptr;    // emission count of each patch (npatch)
+    double* inj_part = nullptr;     // per-block expected counts and clamped patches of the emission
     uint32_t* nflag = nullptr;    // cap neutral: step+1 if the neutral had an event
     uint32_t* prod_list = nullptr;
     int32_t* prod_ev = nullptr;

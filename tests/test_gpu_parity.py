@@ -209,16 +209,20 @@ def test_collide_big_cells():
     compare_states(cfg, g.state(), o.state(), 0.0, 1e-12)
 
 
-@pytest.mark.parametrize("precision", [F64, F32])
-def test_emission_parity(precision):
+@pytest.mark.parametrize("precision,az,field,steps", [(F64, 64, 13e9, 200), (F32, 64, 13e9, 200),
+                                                       (F64, 512, 20e9, 60)])
+def test_emission_parity(precision, az, field, steps):
     """Fowler-Nordheim emission over many steps in a fixed potential: same
-    counts, ids and positions."""
+    counts, ids and positions. With 512 azimuthal patches the surface has
+    17408 patches, more than one pass of the emission kernel takes (8192),
+    the last pass ragged."""
     cfg = W.tiny()
-    cfg.apex_field = 13e9
+    cfg.apex_field = field
+    cfg.fn_az = az
     g = pic.Simulation(cfg, caps=(20000, 1024, 1024), precision=precision)
     o = oracle.Oracle(cfg)
     tot = 0
-    for s in range(200):
+    for s in range(steps):
         g.step(1, pic.STEP_INJECT | pic.STEP_ADVANCE)
         o.step_no = s
         tot += o.inject()
@@ -227,6 +231,19 @@ def test_emission_parity(precision):
     assert m["fn_expected"] == pytest.approx(o.n_expected, rel=1e-9)
     tol = 1e-12 if precision == F64 else 1e-6
     compare_states(cfg, g.state(), o.state(), tol, 0.0)
+
+
+def test_emission_capacity_error():
+    """An emission larger than the free electron slots raises the capacity
+    error at the next synchronizing call; the oracle at this field emits 21
+    electrons in the first step, over the 16 slots given."""
+    cfg = W.tiny()
+    cfg.apex_field = 40e9
+    g = pic.Simulation(cfg, caps=(16, 1024, 1024), precision=F64)
+    with pytest.raises(pic.PicError) as e:
+        g.step(1, pic.STEP_INJECT | pic.STEP_ADVANCE)
+        g.moments()
+    assert e.value.code == -3
 
 
 def test_poisson_solve_parity():
