@@ -79,6 +79,8 @@ struct MgHier {
     int pre, post; // sweeps on the coarse levels (the finest level always does two and two)
     int zm_kc;     // planes per block of the fine sweeps
     unsigned zm_blocks;
+    int rz_kc;     // coarse planes per block of the z-marching restriction to level 1
+    unsigned rz_blocks;  // its grid (0: the plane kernel)
 };
 
 static void mg_dims(const pic_config* cfg, std::vector<int3>& dims) {
@@ -686,6 +688,93 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict2(MgArgs a, int fnx, int 
     store_restricted(C, q.n, s * (double)u, first);
 }
 
+// k_mg_restrict2 marching in z: a thread takes one coarse column over kc
+// coarse planes. Coarse planes Jz and Jz + 1 share the fine planes 2Jz + 1
+// and 2Jz + 2, so a step reads two new fine planes (four rows of four nodes
+// each) and keeps the x-y sums of the other two; the sums and their order
+// are those of k_mg_restrict2, so the results agree bit for bit.
+__global__ __launch_bounds__(kBlock) void k_mg_restrict2z(MgArgs a, int fnx, int fny, int fnz,
+                                                           const mgv* __restrict__ r, MgLevel C, int first, int kc) {
+    if (a.s->done) return;
+    const ZMarch t = zmarch(C.nx, C.ny, C.nz, kc);
+    if (!t.col) return;
+    const int Jx = t.i, Jy = t.j;
+    float wx[4];
+    double wy[4];
+    uint32_t rowo[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const int fi = 2 * Jx - 1 + d, fj = 2 * Jy - 1 + d;
+        wx[d] = (fi >= 0 && fi < fnx) ? (float)interp_w(fi, Jx, C.nx) : 0.0f;
+        wy[d] = (fj >= 0 && fj < fny) ? interp_w(fj, Jy, C.ny) : 0.0;
+        rowo[d] = (uint32_t)(clampi(fj, fny) * fnx);
+    }
+    const uint32_t il = (uint32_t)clampi(2 * Jx - 1, fnx), ip = (uint32_t)(2 * Jx), ir = (uint32_t)clampi(2 * Jx + 2, fnx);
+    const uint32_t fpl = (uint32_t)(fnx * fny);
+    // the 16 values of fine plane fk a coarse node takes (clamped; the z
+    // weight of a plane outside the grid is zero), and their x-y sum
+    struct Pl {
+        float l[4], r[4];
+        float2 p[4];
+    };
+    auto load = [&](int fk, Pl& v) {
+        const uint32_t o = (uint32_t)clampi(fk, fnz) * fpl;
+#pragma unroll
+        for (int dy = 0; dy < 4; ++dy) {
+            v.l[dy] = r[o + rowo[dy] + il];
+            v.p[dy] = *(const float2*)(r + o + rowo[dy] + ip);
+            v.r[dy] = r[o + rowo[dy] + ir];
+        }
+    };
+    auto xysum = [&](const Pl& v) -> double {
+        double sy = 0.0;
+#pragma unroll
+        for (int dy = 0; dy < 4; ++dy) {
+            float sx = wx[0] * v.l[dy];
+            sx = fmaf(wx[1], v.p[dy].x, sx);
+            sx = fmaf(wx[2], v.p[dy].y, sx);
+            sx = fmaf(wx[3], v.r[dy], sx);
+            sy += wy[dy] * (double)sx;
+        }
+        return sy;
+    };
+    // the two new planes of a step are loaded one step ahead
+    Pl a2, a3;
+    double s0, s1;
+    {
+        Pl a0, a1;
+        load(2 * t.k0 - 1, a0);
+        load(2 * t.k0, a1);
+        load(2 * t.k0 + 1, a2);
+        load(2 * t.k0 + 2, a3);
+        s0 = xysum(a0);
+        s1 = xysum(a1);
+    }
+    const int64_t cpl = (int64_t)C.nx * C.ny;
+    int64_t n = (int64_t)t.k0 * cpl + (int64_t)Jy * C.nx + Jx;
+    for (int Jz = t.k0; Jz < t.k1; ++Jz, n += cpl) {
+        const double s2 = xysum(a2), s3 = xysum(a3);
+        if (Jz + 1 < t.k1) {
+            load(2 * Jz + 3, a2);
+            load(2 * Jz + 4, a3);
+        }
+        double wz[4];
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            const int fk = 2 * Jz - 1 + d;
+            wz[d] = (fk >= 0 && fk < fnz) ? interp_w(fk, Jz, C.nz) : 0.0;
+        }
+        double sum = 0.0;
+        sum += wz[0] * s0;
+        sum += wz[1] * s1;
+        sum += wz[2] * s2;
+        sum += wz[3] * s3;
+        store_restricted(C, n, sum * (double)C.used[n], first);
+        s0 = s2;
+        s1 = s3;
+    }
+}
+
 // b_c = P^T r: coarse node J collects the fine nodes 2J-1 .. 2J+2 of each
 // axis with their interpolation weights (zero where J is not an unknown).
 __global__ __launch_bounds__(kBlock) void k_mg_restrict(MgArgs a, int fnx, int fny, int fnz, const mgv* __restrict__ r,
@@ -1173,6 +1262,12 @@ int mg_setup(pic_ctx* c) {
     h->pre = 2;
     h->post = 2;
     h->zm_blocks = zmarch_grid(c->g.nx, c->g.ny, c->g.nz, stencil_target(c), 1, &h->zm_kc);
+    // the restriction to level 1 marches in z where the coarse rows fill a
+    // wavefront (an even fine width, level 1 at least 64 wide)
+    h->rz_kc = 0;
+    h->rz_blocks = 0;
+    if (c->g.nx % 2 == 0 && h->lv[1].nx >= 64)
+        h->rz_blocks = zmarch_grid(h->lv[1].nx, h->lv[1].ny, h->lv[1].nz, 1024, 1, &h->rz_kc);
     // plane grids: nz in gridDim.y, the plane size in 32-bit indices
     if (h->zm_blocks > kMaxStencilBlocks || c->g.nz > 65535 || (int64_t)c->g.nx * c->g.ny >= ((int64_t)1 << 30)) {
         delete h;
@@ -1280,7 +1375,10 @@ float* mg_vcycle(pic_ctx* c, const TB* b0, double* part_rr, double* part_bb, dou
         const MgLevel& F = h->lv[l];
         const MgLevel& C = h->lv[l + 1];
         const int first = l + 1 < nl - 1 ? 1 : 0;
-        if (F.nx % 2 == 0)
+        if (l == 0 && h->rz_blocks)
+            hipLaunchKernelGGL(k_mg_restrict2z, dim3(h->rz_blocks), dim3(kBlock), 0, c->stream, a, F.nx, F.ny, F.nz,
+                               r, C, first, h->rz_kc);
+        else if (F.nx % 2 == 0)
             hipLaunchKernelGGL(k_mg_restrict2, plane_grid(C), dim3(kBlock), 0, c->stream, a, F.nx, F.ny, F.nz, r, C,
                                first);
         else
