@@ -129,7 +129,8 @@ def trace_summary(trace_csv, min_us=10.0):
     import statistics
     rows = list(csv.DictReader(open(trace_csv)))
     res = {}
-    for sym in list(KERNEL_SYMBOLS.values()) + ["k_mcc_small<float>", "k_mcc_cells<float>", "k_mg_sweep_z<false>"]:
+    for sym in list(KERNEL_SYMBOLS.values()) + ["k_mcc_small<float>", "k_mcc_cells<float>", "k_mg_sweep_z<false>",
+                                                  "k_mg_restrict2z"]:
         name = "pic::" + sym
         d = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in rows
              if r["Kernel_Name"].replace("void ", "").startswith(name + "(") or
