@@ -12,7 +12,11 @@ apex) with 20 M particles stored as FP32 SoA (16 M electrons at kT = 5 eV,
 256-node cross-section tables, dt = 5e-17 s. Inputs are generated on the host,
 copied to the GPU and resident in HBM before timing starts.
 
-Prints one JSON line (see the README of the metric fields in the design doc).
+Prints one JSON line: the throughput (value, ms_per_step), the roofline of
+the dominant kernel (k_pcg_b: HIP-event time against the 8 TB/s HBM peak,
+with the HBM bytes measured by rocprofv3 counters when a summary is present),
+the CPU oracle's rate on a bounded sample, and the learned warm start's
+iteration counts.
 """
 from __future__ import annotations
 
@@ -224,8 +228,8 @@ def main():
                          "scales the FETCH_SIZE / WRITE_SIZE counters to bytes) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU layout is "
-              "described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); a multi-GPU run is not built "
+              "(the intended layout: one process per GPU, the grid split into z-slabs)", file=sys.stderr)
         sys.exit(2)
 
     if args.pmc_summary:
