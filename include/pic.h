@@ -24,10 +24,12 @@
  * (pic_moments, pic_events, pic_solve_poisson, pic_inject) synchronize it.
  *
  * Errors: every call returns PIC_OK (0) or a negative pic_status. Device-side
- * conditions (particle capacity, fixed-point overflow, a cell with more
- * particles than the collision kernels accept) are sticky: they are raised by
- * the next synchronizing call and leave the context in a failed state in
- * which every call returns PIC_E_STATE. pic_last_error gives a message.
+ * conditions (particle capacity; a possible fixed-point overflow of the
+ * charge, reported when a tile of 8^3 cells holds 2^20 or more particles, the
+ * count below which no node sum can reach 2^63; a cell with more particles
+ * than the collision kernels accept) are sticky: they are raised by the next
+ * synchronizing call and leave the context in a failed state in which every
+ * call returns PIC_E_STATE. pic_last_error gives a message.
  */
 #ifndef PIC_H
 #define PIC_H
@@ -147,7 +149,11 @@ typedef struct pic_solve_info {
     int32_t iterations;    /* CG iterations (matrix products) */
     int32_t converged;     /* 1 if ||r|| <= rtol ||b|| was reached */
     double relres;         /* final ||r|| / ||b|| (recursively updated residual) */
-    double relres0;        /* ||r|| / ||b|| of the initial guess */
+    double relres0;        /* ||r|| / ||b|| of the initial guess the solve started from */
+    int32_t fell_back;     /* PIC_GUESS_LEARNED with the fallback on: 1 if the network's guess was not finite
+                              or had a larger initial residual than V0 phi1, which the solve then started
+                              from instead */
+    int32_t reserved;
 } pic_solve_info;
 
 typedef struct pic_moments_t {
@@ -185,10 +191,17 @@ typedef struct pic_ctx pic_ctx;
  * capacities (cap[3] particles per species). */
 pic_status pic_scratch_size(const pic_config* cfg, const int64_t cap[3], size_t* bytes);
 
-/* Create a context. Validates cfg (INVALID_ARG), computes the node types,
- * solves the unit-anode Laplace problem to cfg->laplace_rtol (phi1, field0),
- * sets V0 = apex_field / (Laplace apex field per volt), phi = V0 phi1 and the
- * node field, and empties all species. Synchronizes the stream. */
+/* Create a context: the statement of the problem of Sec. 2.1 (Eq. poi with
+ * the boundary conditions bcf1-bcf3) on the node grid. Validates cfg
+ * (INVALID_ARG), computes the node types (0 V on the cathode plane and inside
+ * or on the tip, V0 on the anode plane, zero normal field on the lateral
+ * faces), solves the unit-anode Laplace problem to cfg->laplace_rtol (phi1,
+ * and its field field0, the weighting field of the Shockley-Ramo current of
+ * Sec. 2.3.1), sets V0 = apex_field / (Laplace apex field per volt),
+ * phi = V0 phi1 and the node field, and empties all species. bufs and the
+ * stream are borrowed, not owned. Synchronizes the stream. Errors:
+ * INVALID_ARG (config, NULL or misaligned buffers, scratch too small), HIP,
+ * NOT_CONVERGED (Laplace solve). */
 pic_status pic_init(const pic_config* cfg, const pic_buffers* bufs, void* hip_stream, pic_ctx** out);
 
 /* With src != NULL: append src->n particles of one species (copied from
@@ -203,14 +216,22 @@ pic_status pic_inject(pic_ctx* ctx, const pic_particles* src, int64_t* n_added);
  * convergence). */
 pic_status pic_step(pic_ctx* ctx, int32_t nsteps, uint32_t flags);
 
-/* Solve Eq. poi for the charge in rho with the given solver and guess until
- * ||b - A phi|| <= rtol ||b|| or maxit iterations, then compute the node field.
+/* Solve Eq. poi (Sec. 2.1, with bcf1-bcf3) for the charge in rho with the
+ * given solver and guess until ||b - A phi|| <= rtol ||b|| or maxit
+ * iterations, then compute the node field. With PIC_GUESS_LEARNED the initial
+ * residual of the network's guess is compared with that of V0 phi1 first; a
+ * guess that is not finite or is worse is replaced by V0 phi1 (info->fell_back),
+ * so the result never depends on the network, only the iteration count does.
  * Returns NOT_CONVERGED (context stays usable) when maxit is reached. */
 pic_status pic_solve_poisson(pic_ctx* ctx, int32_t solver, int32_t guess, double rtol, int32_t maxit,
                              pic_solve_info* info);
 
-/* Reductions over the current state; synchronizes and reports sticky
- * device errors. */
+/* Observables of the current state (the particle counts and event counts
+ * of Sec. 3.2, the Shockley-Ramo gap current I = sum q v . E0 of Sec. 2.3.1
+ * with E0 = field0, kinetic energies, removals per boundary, emission and
+ * solver statistics) by fixed-order reductions, copied to the caller's host
+ * struct. Synchronizes the stream and reports sticky device errors
+ * (CAPACITY, OVERFLOW), after which the context is in a failed state. */
 pic_status pic_moments(pic_ctx* ctx, pic_moments_t* out);
 
 /* Copy up to cap events of the last collide phase run with PIC_STEP_EVENTS;
@@ -321,9 +342,14 @@ void unet_destroy(unet* net);
  * network's own scale; project = 1: gamma = (y.q) / (y.L y), q the charge
  * term and L the operator of Eq. poi, the weight that minimizes the energy
  * norm of the error along y (the guess is then never worse in that norm than
- * V0 phi1; one extra pass over the grid). Invalid arguments:
- * PIC_E_INVALID_ARG. */
-pic_status pic_set_learned_guess(pic_ctx* ctx, unet* net, int32_t smooth_passes, int32_t project);
+ * V0 phi1; one extra pass over the grid). fallback = 1: plain CG judges the
+ * guess before every solve (the initial residuals of the guess and of V0 phi1,
+ * one residual pass each) and starts from V0 phi1 instead when the network's
+ * guess is not finite or has the larger residual (pic_solve_info.fell_back);
+ * fallback = 0: the network's guess is used as it is (for inspecting it).
+ * Invalid arguments: PIC_E_INVALID_ARG. */
+pic_status pic_set_learned_guess(pic_ctx* ctx, unet* net, int32_t smooth_passes, int32_t project,
+                                 int32_t fallback);
 /* A training pair from the current state: x = q / s from rho and
  * y = (phi - V0 phi1) eps0 h / (e s) from phi (solve to a tight tolerance
  * first). x, y: device fp32 [nz][ny][nx]; scale (optional, host) receives s

@@ -12,8 +12,10 @@ ionization, charge deposition, Poisson solve and node field.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
+import shutil
 import subprocess
 
 import numpy as np
@@ -75,49 +77,79 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB_PATH):
             build()
-        L = C.CDLL(_LIB_PATH)
-        dp, u8p, i64p, u32p = (np.ctypeslib.ndpointer(t, flags="C") for t in
-                               (np.float64, np.uint8, np.int64, np.uint32))
-        cfgp = C.POINTER(_Config)
-        L.orc_constants.argtypes = [dp]
-        L.orc_philox.argtypes = [u32p, u32p, u32p]
-        L.orc_uniform.argtypes = [C.c_uint32, C.c_uint32]
-        L.orc_uniform.restype = C.c_double
-        L.orc_inside_tip.argtypes = [cfgp, C.c_double, C.c_double, C.c_double]
-        L.orc_node_types.argtypes = [cfgp, u8p]
-        L.orc_rhs.argtypes = [cfgp, u8p, i64p, C.c_double, dp]
-        L.orc_apply_A.argtypes = [cfgp, u8p, dp, dp]
-        L.orc_solve.argtypes = [cfgp, u8p, i64p, C.c_double, dp, C.c_double, C.c_int, C.POINTER(C.c_double)]
-        L.orc_solve.restype = C.c_int
-        L.orc_field.argtypes = [cfgp, dp, dp]
-        L.orc_gather.argtypes = [cfgp, dp, C.c_double, C.c_double, C.c_double, dp]
-        L.orc_interp_phi.argtypes = [cfgp, dp, C.c_double, C.c_double, C.c_double]
-        L.orc_interp_phi.restype = C.c_double
-        L.orc_apex_field.argtypes = [cfgp, dp]
-        L.orc_apex_field.restype = C.c_double
-        L.orc_push.argtypes = [cfgp, dp, C.POINTER(_Species), C.c_double, C.c_double,
-                               np.ctypeslib.ndpointer(np.int32, flags="C")]
-        L.orc_deposit.argtypes = [cfgp, C.POINTER(_Species), C.c_int64, i64p]
-        L.orc_cell_of.argtypes = [cfgp, C.c_double, C.c_double, C.c_double]
-        L.orc_cell_of.restype = C.c_int64
-        L.orc_xs.argtypes = [cfgp, dp, C.c_double]
-        L.orc_xs.restype = C.c_double
-        L.orc_adk_rate.argtypes = [cfgp, C.c_double]
-        L.orc_adk_rate.restype = C.c_double
-        L.orc_fn_current.argtypes = [cfgp, C.c_double, C.POINTER(C.c_int)]
-        L.orc_fn_current.restype = C.c_double
-        L.orc_fn_patch_count.argtypes = [cfgp]
-        L.orc_fn_patch_count.restype = C.c_int64
-        L.orc_fn_patch.argtypes = [cfgp, C.c_int64, C.c_double, C.c_double, dp]
-        L.orc_fn_inject.argtypes = [cfgp, C.c_uint32, dp, C.POINTER(_Species), C.POINTER(C.c_uint32),
-                                    C.POINTER(C.c_double), C.POINTER(C.c_int64)]
-        L.orc_fn_inject.restype = C.c_int64
-        L.orc_collide.argtypes = [cfgp, C.c_uint32, C.c_int32, dp, C.POINTER(_Species),
-                                  C.POINTER(C.c_uint32), C.POINTER(_CollideOut)]
-        L.orc_collide.restype = C.c_int
-        L.orc_moments.argtypes = [cfgp, C.POINTER(_Species), dp, dp]
-        _lib = L
+        _lib = _load(_LIB_PATH)
     return _lib
+
+
+@contextlib.contextmanager
+def use_library(path: str):
+    """Run the block with the oracle functions taken from another build of
+    oracle.c (the mutation tests build copies with a planted mistake)."""
+    global _lib
+    saved = _lib
+    _lib = _load(path)
+    try:
+        yield _lib
+    finally:
+        _lib = saved
+
+
+def build_copy(src_text: str, out_dir: str) -> str:
+    """Compile the given text of oracle.c (same flags as build()) into
+    out_dir and return the library path."""
+    src = os.path.join(out_dir, "oracle_copy.c")
+    with open(src, "w") as f:
+        f.write(src_text)
+    shutil.copy(os.path.join(_HERE, "oracle.h"), os.path.join(out_dir, "oracle.h"))
+    out = os.path.join(out_dir, "liboracle_copy.so")
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+                    "-o", out, src, "-lm"], check=True)
+    return out
+
+
+def _load(path: str):
+    L = C.CDLL(path)
+    dp, u8p, i64p, u32p = (np.ctypeslib.ndpointer(t, flags="C") for t in
+                           (np.float64, np.uint8, np.int64, np.uint32))
+    cfgp = C.POINTER(_Config)
+    L.orc_constants.argtypes = [dp]
+    L.orc_philox.argtypes = [u32p, u32p, u32p]
+    L.orc_uniform.argtypes = [C.c_uint32, C.c_uint32]
+    L.orc_uniform.restype = C.c_double
+    L.orc_inside_tip.argtypes = [cfgp, C.c_double, C.c_double, C.c_double]
+    L.orc_node_types.argtypes = [cfgp, u8p]
+    L.orc_rhs.argtypes = [cfgp, u8p, i64p, C.c_double, dp]
+    L.orc_apply_A.argtypes = [cfgp, u8p, dp, dp]
+    L.orc_solve.argtypes = [cfgp, u8p, i64p, C.c_double, dp, C.c_double, C.c_int, C.POINTER(C.c_double)]
+    L.orc_solve.restype = C.c_int
+    L.orc_field.argtypes = [cfgp, dp, dp]
+    L.orc_gather.argtypes = [cfgp, dp, C.c_double, C.c_double, C.c_double, dp]
+    L.orc_interp_phi.argtypes = [cfgp, dp, C.c_double, C.c_double, C.c_double]
+    L.orc_interp_phi.restype = C.c_double
+    L.orc_apex_field.argtypes = [cfgp, dp]
+    L.orc_apex_field.restype = C.c_double
+    L.orc_push.argtypes = [cfgp, dp, C.POINTER(_Species), C.c_double, C.c_double,
+                           np.ctypeslib.ndpointer(np.int32, flags="C")]
+    L.orc_deposit.argtypes = [cfgp, C.POINTER(_Species), C.c_int64, i64p]
+    L.orc_cell_of.argtypes = [cfgp, C.c_double, C.c_double, C.c_double]
+    L.orc_cell_of.restype = C.c_int64
+    L.orc_xs.argtypes = [cfgp, dp, C.c_double]
+    L.orc_xs.restype = C.c_double
+    L.orc_adk_rate.argtypes = [cfgp, C.c_double]
+    L.orc_adk_rate.restype = C.c_double
+    L.orc_fn_current.argtypes = [cfgp, C.c_double, C.POINTER(C.c_int)]
+    L.orc_fn_current.restype = C.c_double
+    L.orc_fn_patch_count.argtypes = [cfgp]
+    L.orc_fn_patch_count.restype = C.c_int64
+    L.orc_fn_patch.argtypes = [cfgp, C.c_int64, C.c_double, C.c_double, dp]
+    L.orc_fn_inject.argtypes = [cfgp, C.c_uint32, dp, C.POINTER(_Species), C.POINTER(C.c_uint32),
+                                C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.orc_fn_inject.restype = C.c_int64
+    L.orc_collide.argtypes = [cfgp, C.c_uint32, C.c_int32, dp, C.POINTER(_Species),
+                              C.POINTER(C.c_uint32), C.POINTER(_CollideOut)]
+    L.orc_collide.restype = C.c_int
+    L.orc_moments.argtypes = [cfgp, C.POINTER(_Species), dp, dp]
+    return L
 
 
 def make_config(cfg) -> tuple[_Config, list]:

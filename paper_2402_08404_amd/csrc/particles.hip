@@ -246,7 +246,15 @@ struct DepositArgs {
     const uint32_t* bins;
     int64_t* rho;
     Grid g;
+    DevState* st;
 };
+
+// A node takes charge only from the particles of the (at most 8) cells
+// around it, which lie in at most 8 tiles; each particle adds at most 2^40
+// units. With fewer than 2^20 particles per tile every node sum stays below
+// 8 * 2^20 * 2^40 = 2^63, so a tile at or above that count is reported as a
+// possible fixed-point overflow (sticky PIC_E_OVERFLOW).
+constexpr uint32_t kTileOverflow = 1u << 20;
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_deposit_tiles(DepositArgs<T> a) {
@@ -256,6 +264,10 @@ __global__ __launch_bounds__(kBlock) void k_deposit_tiles(DepositArgs<T> a) {
     uint32_t tile = blockIdx.x;
     uint32_t b0 = a.off[(int64_t)tile * kTileCells], b1 = a.off[(int64_t)(tile + 1) * kTileCells];
     if (b0 == b1) return;
+    if (b1 - b0 >= kTileOverflow) {
+        if (threadIdx.x == 0) atomicCAS(&a.st->error, 0, PIC_E_OVERFLOW);
+        return;
+    }
     int tx = (int)(tile % g.ntx), ty = (int)((tile / g.ntx) % g.nty), tz = (int)(tile / (g.ntx * g.nty));
     int ox = tx * kTile, oy = ty * kTile, oz = tz * kTile;
     for (int m = threadIdx.x; m < N1 * N1 * N1; m += blockDim.x) q[m] = 0ull;
@@ -1129,6 +1141,7 @@ static hipError_t bin_t(pic_ctx* c) {
     d.bins = c->bins;
     d.rho = c->buf.rho;
     d.g = g;
+    d.st = c->st;
     int td = tic(c, PIC_T_DEPOSIT);
     hipLaunchKernelGGL(k_deposit_tiles<T>, dim3((unsigned)(g.nkeys / kTileCells)), dim3(kBlock), 0, c->stream, d);
     toc(c, td);

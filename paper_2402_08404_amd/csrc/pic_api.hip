@@ -323,8 +323,10 @@ static pic_status sync_state(pic_ctx* c) {
     if (s != PIC_OK) return s;
     if (c->host_st->error != 0) {
         int e = c->host_st->error;
-        return fail(c, e, e == PIC_E_CAPACITY ? "particle capacity exceeded (or a cell holds more than 4096 particles)"
-                                               : "device error");
+        return fail(c, e, e == PIC_E_CAPACITY   ? "particle capacity exceeded (or a cell holds more than 4096 particles)"
+                          : e == PIC_E_OVERFLOW ? "possible fixed-point charge overflow: a tile of 8^3 cells holds 2^20 "
+                                                  "or more particles"
+                                                : "device error");
     }
     return PIC_OK;
 }
@@ -364,8 +366,29 @@ static pic_status solve(pic_ctx* c, int solver, int guess, double rtol, int maxi
     if (!info) info = &tmp;
     int th = tic(c, PIC_T_SOLVE);
     int r;
-    if (guess == PIC_GUESS_LAPLACE || guess == PIC_GUESS_LEARNED) {
-        r = guess_phi(c, guess == PIC_GUESS_LEARNED);
+    int fell_back = 0;
+    if (guess == PIC_GUESS_LEARNED && !c->learn_fallback) {
+        r = guess_phi(c, true);
+        if (r != 0) return fail(c, PIC_E_HIP, "warm start failed");
+        guess = PIC_GUESS_PREVIOUS;
+    } else if (guess == PIC_GUESS_LEARNED) {
+        // The network's guess is judged against V0 phi1 by the initial
+        // residual of each (a zero-iteration CG pass: the residual and its
+        // norm only); a guess that is not finite, or worse, is replaced.
+        pic_solve_info i_plain{}, i_net{};
+        r = guess_phi(c, false);
+        if (r == 0) r = cg_solve(c, c->buf.phi, c->V0, c->buf.rho, PIC_GUESS_PREVIOUS, rtol, 0, &i_plain);
+        if (r == 0) r = guess_phi(c, true);
+        if (r == 0) r = cg_solve(c, c->buf.phi, c->V0, c->buf.rho, PIC_GUESS_PREVIOUS, rtol, 0, &i_net);
+        if (r != 0) return fail(c, PIC_E_HIP, "warm start failed");
+        fell_back = c->host_st->learn_bad || !std::isfinite(i_net.relres0) || !(i_net.relres0 <= i_plain.relres0);
+        if (fell_back) {
+            r = guess_phi(c, false);
+            if (r != 0) return fail(c, PIC_E_HIP, "warm start failed");
+        }
+        guess = PIC_GUESS_PREVIOUS;
+    } else if (guess == PIC_GUESS_LAPLACE) {
+        r = guess_phi(c, false);
         if (r != 0) return fail(c, PIC_E_HIP, "warm start failed");
         guess = PIC_GUESS_PREVIOUS;
     }
@@ -377,6 +400,7 @@ static pic_status solve(pic_ctx* c, int solver, int guess, double rtol, int maxi
         r = mixed_solve(c, c->buf.phi, c->V0, c->buf.rho, guess, rtol, maxit, info);
     if (r == -3) return fail(c, PIC_E_INVALID_ARG, "solver not available for this configuration");
     if (r != 0) return fail(c, PIC_E_HIP, "solver failed");
+    info->fell_back = fell_back;
     c->last_solve = *info;
     c->cg_iters_total += info->iterations;
     pic_status s = hip_check(c, launch_field(c, c->buf.phi, c->buf.field), "field");

@@ -56,6 +56,7 @@ struct DevState {
     // weight of the network output y in the guess V0 phi1 + gamma y
     double learn_scale;
     double learn_gamma;
+    int learn_bad;                     // the network output of the last learned guess was not finite
 };
 
 // Cells are numbered tile-major: tiles of kTile^3 cells, tile index
@@ -417,6 +418,7 @@ struct pic_ctx {
     int last_iters[3] = {0, 0, 0};   // iterations of the last solve per solver (first launch chunk)
     int learn_smooth = 0;            // binomial filter passes on its output
     int learn_project = 1;           // weight the network output by the energy-norm projection
+    int learn_fallback = 1;          // judge the learned guess against V0 phi1 before each solve
     double* phi_prev = nullptr;      // potential of the previous step solve (extrapolated guess)
     int phi_hist = 0;                // consecutive step solves whose potential phi_prev / phi hold
     // host state

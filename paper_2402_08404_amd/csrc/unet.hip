@@ -1223,15 +1223,16 @@ __global__ void k_learn_smooth(const float* __restrict__ yi, float* __restrict__
     }
 }
 
-// phi = V0 phi1 + (e s / (eps0 h)) y on free nodes, V0 phi1 on fixed nodes
-// phi = V0 phi1 + gamma y on free nodes (gamma from st), V0 phi1 elsewhere
-// and without a network output
+// phi = V0 phi1 + gamma y on free nodes (gamma from st), V0 phi1 elsewhere,
+// without a network output and when gamma is zero (which it is when the
+// network output was not finite: 0 * NaN must not reach the guess)
 __global__ void k_learn_phi(const double* __restrict__ phi1, const float* __restrict__ y, const uint8_t* __restrict__ type,
                             int64_t n, double V0, const DevState* st, double* __restrict__ phi) {
     const double gam = st->learn_gamma;
+    const bool use_y = y && gam != 0.0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         double v = V0 * phi1[i];
-        if (y && type[i] == 0) v += gam * (double)y[i];
+        if (use_y && type[i] == 0) v += gam * (double)y[i];
         phi[i] = v;
     }
 }
@@ -1278,7 +1279,8 @@ __global__ __launch_bounds__(kBlock) void k_learn_proj(Grid g, const float* __re
 }
 
 // gamma: the projection weight (project != 0), else the network's own
-// scaling e s / (eps0 h)
+// scaling e s / (eps0 h); zero, with learn_bad set, when y.q or y.L y is not
+// finite (a network output with NaN or infinity anywhere on a free node)
 __global__ void k_learn_gamma(const double* __restrict__ part, int nparts, int project, double c0, DevState* st) {
     if (threadIdx.x != 0) return;
     double a = 0.0, b = 0.0;
@@ -1286,7 +1288,10 @@ __global__ void k_learn_gamma(const double* __restrict__ part, int nparts, int p
         a += part[2 * i];
         b += part[2 * i + 1];
     }
-    st->learn_gamma = project ? (b > 0.0 ? a / b : 0.0) : (st->learn_scale > 0.0 ? c0 * st->learn_scale : 0.0);
+    const bool bad = !isfinite(a) || !isfinite(b);
+    st->learn_bad = bad ? 1 : 0;
+    double g = project ? (b > 0.0 ? a / b : 0.0) : (st->learn_scale > 0.0 ? c0 * st->learn_scale : 0.0);
+    st->learn_gamma = (bad || !isfinite(g)) ? 0.0 : g;
 }
 
 // y = (phi - V0 phi1) eps0 h / (e s) on free nodes, zero elsewhere
@@ -1346,13 +1351,15 @@ int guess_phi(pic_ctx* c, bool with_net) {
 
 extern "C" {
 
-pic_status pic_set_learned_guess(pic_ctx* c, unet* u, int32_t smooth_passes, int32_t project) {
-    if (!c || smooth_passes < 0 || smooth_passes > 64 || project < 0 || project > 1) return PIC_E_INVALID_ARG;
+pic_status pic_set_learned_guess(pic_ctx* c, unet* u, int32_t smooth_passes, int32_t project, int32_t fallback) {
+    if (!c || smooth_passes < 0 || smooth_passes > 64 || project < 0 || project > 1 || fallback < 0 || fallback > 1)
+        return PIC_E_INVALID_ARG;
     if (u && (u->B != 1 || u->D != c->cfg.nz || u->H != c->cfg.ny || u->W != c->cfg.nx || u->stream != c->stream))
         return PIC_E_INVALID_ARG;
     c->learned = u;
     c->learn_smooth = smooth_passes;
     c->learn_project = project;
+    c->learn_fallback = fallback;
     return PIC_OK;
 }
 

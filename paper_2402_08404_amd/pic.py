@@ -63,7 +63,8 @@ class pic_particles(C.Structure):
 
 
 class pic_solve_info(C.Structure):
-    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("relres", C.c_double), ("relres0", C.c_double)]
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32), ("relres", C.c_double), ("relres0", C.c_double),
+                ("fell_back", C.c_int32), ("reserved", C.c_int32)]
 
 
 class pic_moments_t(C.Structure):
@@ -121,7 +122,7 @@ def lib():
         L.unet_sync_params.argtypes = [vp]
         L.unet_destroy.argtypes = [vp]
         L.unet_destroy.restype = None
-        L.pic_set_learned_guess.argtypes = [vp, vp, C.c_int32, C.c_int32]
+        L.pic_set_learned_guess.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32]
         L.pic_training_sample.argtypes = [vp, vp, vp, C.POINTER(C.c_double)]
         for f in ("pic_scratch_size", "pic_init", "pic_inject", "pic_step", "pic_solve_poisson", "pic_moments",
                   "pic_events", "unet_param_count", "unet_workspace_size", "unet_create", "unet_forward",
@@ -173,7 +174,7 @@ def pic_solve_poisson(ctx, solver: int, guess: int, rtol: float, maxit: int, all
     if code != PIC_OK and not (allow_unconverged and code == -5):
         _check(code, ctx)
     return {"iterations": info.iterations, "converged": bool(info.converged), "relres": info.relres,
-            "relres0": info.relres0}
+            "relres0": info.relres0, "fell_back": bool(info.fell_back)}
 
 
 def pic_moments(ctx) -> dict:
@@ -264,11 +265,12 @@ def unet_destroy(net):
     lib().unet_destroy(net)
 
 
-def pic_set_learned_guess(ctx, net, smooth_passes: int = 0, project: bool = True):
+def pic_set_learned_guess(ctx, net, smooth_passes: int = 0, project: bool = True, fallback: bool = True):
     """Attach a network for PIC_GUESS_LEARNED (None detaches); with project
-    the network output is weighted by the energy-norm projection (see
+    the network output is weighted by the energy-norm projection, with
+    fallback plain CG judges the guess against V0 phi1 before each solve (see
     include/pic.h)."""
-    _check(lib().pic_set_learned_guess(ctx, net, smooth_passes, 1 if project else 0), ctx)
+    _check(lib().pic_set_learned_guess(ctx, net, smooth_passes, 1 if project else 0, 1 if fallback else 0), ctx)
 
 
 def pic_training_sample(ctx, x: int, y: int) -> float:

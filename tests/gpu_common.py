@@ -1,6 +1,7 @@
 """Helpers of the GPU parity tests: build a GPU instance and an oracle
 instance from the same seeded inputs and compare them particle by particle."""
 import numpy as np
+from scipy.constants import e as sc_e, m_e as sc_me
 
 import oracle
 from paper_2402_08404_amd import workloads as W
@@ -28,10 +29,44 @@ def boundary_margin(cfg, X, Y, Z):
                               np.abs(Y), np.abs(Y - (cfg.ny - 1)), d_tip])
 
 
-def compare_states(cfg, gpu_st, orc_st, pos_tol, vel_tol, margin_tol=None):
+# FP32 unit roundoff
+U32 = 2.0 ** -24
+
+
+def kick_bounds(cfg, pre_state, E):
+    """Per particle (by id), a bound of the FP32 rounding error of the kick
+    (q/m) E dt of one push from the state pre_state, against the same kick in
+    FP64 from the same (FP32-representable) state. The FP32 push stores the
+    node field rounded to FP32 (u |E| per component), forms each trilinear
+    weight with at most three roundings, and sums eight products in sequence
+    (gamma_8 <= 8u of the sum of |w E|), then multiplies by the FP32 rounding
+    of kq = (q/m) dt^2 / h (two more roundings): at most 14u |kq| max|E| over
+    the eight corners of the cell of x^n; 16u is taken. The add v + kick
+    itself rounds by u |v'| (checked separately)."""
+    kq = (-sc_e / sc_me * cfg.dt ** 2 / cfg.h, sc_e / cfg.m_ion * cfg.dt ** 2 / cfg.h, 0.0)
+    Eabs = np.abs(np.asarray(E, np.float64).reshape(cfg.nz, cfg.ny, cfg.nx, 3)).max(axis=3)
+    out = []
+    for s in range(3):
+        d = pre_state[s]
+        i = np.clip(np.floor(d["x"]).astype(np.int64), 0, cfg.nx - 2)
+        j = np.clip(np.floor(d["y"]).astype(np.int64), 0, cfg.ny - 2)
+        k = np.clip(np.floor(d["z"]).astype(np.int64), 0, cfg.nz - 2)
+        m = np.zeros(len(i))
+        for dk in (0, 1):
+            for dj in (0, 1):
+                for di in (0, 1):
+                    m = np.maximum(m, Eabs[k + dk, j + dj, i + di])
+        out.append(dict(zip((int(v) for v in d["id"]), 16 * U32 * abs(kq[s]) * m)))
+    return out
+
+
+def compare_states(cfg, gpu_st, orc_st, pos_tol, vel_tol, margin_tol=None, kick=None):
     """Compare alive particles by id. Particles present on one side only must
     sit within margin_tol of a removal surface on the oracle side (or in its
-    pre-push state). Returns the number of compared particles."""
+    pre-push state). Velocities: within vel_tol relative (plus 1e-3 of the
+    largest speed), or, with kick (from kick_bounds, FP32 pushes), within
+    2u |v'| plus the particle's kick bound. Returns the number of compared
+    particles."""
     n = 0
     for s in range(3):
         g, o = gpu_st[s], orc_st[s]
@@ -57,10 +92,18 @@ def compare_states(cfg, gpu_st, orc_st, pos_tol, vel_tol, margin_tol=None):
         for k in ("x", "y", "z"):
             d = np.abs(g[k][a] - o[k][b])
             assert (d <= pos_tol * np.maximum(1.0, np.abs(o[k][b]))).all(), (s, k, d.max())
-        vs = max(np.abs(np.concatenate([o["vx"][b], o["vy"][b], o["vz"][b]])).max(), 1e-300)
-        for k in ("vx", "vy", "vz"):
-            d = np.abs(g[k][a] - o[k][b])
-            assert (d <= vel_tol * (np.abs(o[k][b]) + 1e-3 * vs)).all(), (s, k, (d / (np.abs(o[k][b]) + 1e-3 * vs)).max())
+        if kick is not None:
+            kb = np.array([kick[s][i] for i in common])
+            for k in ("vx", "vy", "vz"):
+                d = np.abs(g[k][a] - o[k][b])
+                bound = 2 * U32 * np.abs(o[k][b]) + kb
+                assert (d <= bound).all(), (s, k, (d / np.maximum(bound, 1e-300)).max())
+        else:
+            vs = max(np.abs(np.concatenate([o["vx"][b], o["vy"][b], o["vz"][b]])).max(), 1e-300)
+            for k in ("vx", "vy", "vz"):
+                d = np.abs(g[k][a] - o[k][b])
+                assert (d <= vel_tol * (np.abs(o[k][b]) + 1e-3 * vs)).all(), \
+                    (s, k, (d / (np.abs(o[k][b]) + 1e-3 * vs)).max())
         n += len(common)
     return n
 

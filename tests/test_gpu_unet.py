@@ -181,7 +181,8 @@ def test_learned_guess_solve():
     guesses = {}
     for name, g, proj in (("laplace", pic.PIC_GUESS_LAPLACE, False), ("learned_raw", pic.PIC_GUESS_LEARNED, False),
                           ("learned", pic.PIC_GUESS_LEARNED, True)):
-        pic.pic_set_learned_guess(sim.ctx, guess_net.net, 0, proj)
+        # the guesses themselves, without the fallback judge
+        pic.pic_set_learned_guess(sim.ctx, guess_net.net, 0, proj, fallback=False)
         sim.solve(solver=pic.PIC_SOLVER_CG, guess=g, rtol=1e-12, maxit=0, allow_unconverged=True)
         guesses[name] = sim.grid("phi").copy()
     resp = np.linalg.norm(exact - guesses["laplace"])
@@ -210,7 +211,7 @@ def test_learned_guess_solve():
                                   ("learned+2", pic.PIC_GUESS_LEARNED, 2, True)):
             pic.pic_set_learned_guess(sim.ctx, guess_net.net, sm, proj)
             r = sim.solve(solver=solver, guess=g, rtol=1e-8, maxit=100000)
-            res[(solver, name)] = (r["iterations"], round(r["relres0"], 4))
+            res[(solver, name)] = (r["iterations"], round(r["relres0"], 4), r["fell_back"])
             phi = sim.grid("phi")
             assert np.linalg.norm(phi - exact) < 1e-5 * np.linalg.norm(exact)
     print("iterations (solver, guess) -> (iterations, initial relative residual)", res, flush=True)
@@ -218,3 +219,37 @@ def test_learned_guess_solve():
     sim.close()
     guess_net.close()
     train_net.close()
+
+
+@pytest.mark.parametrize("fill", ["nan", "zero"])
+def test_learned_guess_fallback(fill):
+    """Plain CG judges the learned guess: a network whose weights are NaN gives
+    a non-finite output, the solve falls back to V0 phi1 (fell_back), starts
+    from its residual and converges to the plain tolerance in the iterations of
+    the plain solve from V0 phi1; a network with zero weights gives the
+    guess V0 phi1 itself, which is not worse, so nothing falls back."""
+    from paper_2402_08404_amd import pic
+    from paper_2402_08404_amd import workloads as W
+    cfg = W.tiny()
+    sim = pic.Simulation(cfg, caps=(100000, 10000, 4000), precision=pic.PIC_F64)
+    sim.load(W.initial_load(cfg, counts=(20000, 200, 2000), seed=4))
+    sim.step(1, pic.STEP_DEPOSIT)
+    p = np.full(pic.UNet(1, cfg.nz, cfg.ny, cfg.nx).n_params, np.nan if fill == "nan" else 0.0, np.float32)
+    net = pic.UNet(1, cfg.nz, cfg.ny, cfg.nx, params=p)
+    net.sync()
+    plain = sim.solve(solver=pic.PIC_SOLVER_CG, guess=pic.PIC_GUESS_LAPLACE, rtol=1e-8, maxit=100000)
+    phi_plain = sim.grid("phi").copy()
+    for project in (True, False):
+        pic.pic_set_learned_guess(sim.ctx, net.net, 0, project)
+        r = sim.solve(solver=pic.PIC_SOLVER_CG, guess=pic.PIC_GUESS_LEARNED, rtol=1e-8, maxit=100000)
+        print(fill, project, r, plain, flush=True)
+        assert r["converged"] and r["relres"] <= 1e-8
+        assert r["fell_back"] == (fill == "nan")
+        assert r["relres0"] == pytest.approx(plain["relres0"], rel=1e-12)
+        assert r["iterations"] == plain["iterations"]
+        phi = sim.grid("phi")
+        assert np.all(np.isfinite(phi))
+        assert np.abs(phi - phi_plain).max() <= 1e-12 * np.abs(phi_plain).max()
+    pic.pic_set_learned_guess(sim.ctx, None)
+    sim.close()
+    net.close()

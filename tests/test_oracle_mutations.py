@@ -1,0 +1,58 @@
+"""Each pin of tests/test_oracle_readings.py must catch the plausible mistake
+it is there for. A copy of oracle.c with that one mistake planted is built
+on the CPU, and the pin, run against the copy, must fail; the same pin passes
+on the real oracle (tests/test_oracle_readings.py)."""
+import os
+
+import pytest
+
+import oracle
+import test_oracle_readings as R
+
+_SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
+
+# (name, text in oracle.c, planted replacement, pin that must fail)
+MUTATIONS = [
+    ("unshifted pairing",
+     "int64_t shift = (int64_t)floor(uc * (double)NT);",
+     "int64_t shift = 0 * (int64_t)floor(uc * (double)NT);", R.pin_pairing),
+    ("tie goes to the neutral",
+     "int a_is_proj = NA <= NB;", "int a_is_proj = NA < NB;", R.pin_pairing),
+    ("targets in descending id order",
+     "const entry* te = &ent[T0 + (shift + i) % NT];",
+     "const entry* te = &ent[T0 + NT - 1 - (shift + i) % NT];", R.pin_pairing),
+    ("R instead of its inverse for (theta, phi)",
+     "    du[0] = ct * cp * w0 - sp * w1 + st * cp * w2;\n"
+     "    du[1] = ct * sp * w0 + cp * w1 + st * sp * w2;\n"
+     "    du[2] = -st * w0 + ct * w2;",
+     "    du[0] = ct * cp * w0 + ct * sp * w1 - st * w2;\n"
+     "    du[1] = -sp * w0 + cp * w1;\n"
+     "    du[2] = st * cp * w0 + st * sp * w1 + ct * w2;", R.pin_elastic_du),
+    ("R instead of its inverse for (theta', phi')",
+     "double w0 = um * st2 * cos(ph2), w1 = um * st2 * sin(ph2), w2 = um * (ct2 - 1.0);",
+     "double w0 = -um * st2, w1 = 0.0 * ph2, w2 = um * (ct2 - 1.0);", R.pin_elastic_du),
+    ("no (e,Cu) exclusion in the (Cu+,Cu) pairing",
+     "if (cls == 2 && used[sb][ib]) continue;", "", R.pin_priority),
+    ("no impact exclusion in field ionization",
+     "if (used[ORC_SP_NEU][p]) continue;", "", R.pin_priority),
+    ("(Cu+,Cu) before (e,Cu)",
+     "    if (flags & ORC_COLL_MCC1) mcc_class(c, step, 1, ent, ne, sp, used, prod, &nprod, o);\n"
+     "    if (flags & ORC_COLL_MCC2) mcc_class(c, step, 2, ent, ne, sp, used, prod, &nprod, o);",
+     "    if (flags & ORC_COLL_MCC2) mcc_class(c, step, 2, ent, ne, sp, used, prod, &nprod, o);\n"
+     "    if (flags & ORC_COLL_MCC1) mcc_class(c, step, 1, ent, ne, sp, used, prod, &nprod, o);", R.pin_priority),
+    ("emission field half a spacing out",
+     "g[0] + g[3], g[1] + g[4], g[2] + g[5]) / h;",
+     "g[0] + 0.5 * g[3], g[1] + 0.5 * g[4], g[2] + 0.5 * g[5]) / (0.5 * h);", R.pin_emission_field_point),
+    ("emission field from the surface potential",
+     "g[0] + g[3], g[1] + g[4], g[2] + g[5]) / h;", "g[0], g[1], g[2] + 1.0) / h;", R.pin_emission_field_point),
+]
+
+
+@pytest.mark.parametrize("name,old,new,pin", MUTATIONS, ids=[m[0] for m in MUTATIONS])
+def test_pin_catches_planted_mistake(tmp_path, name, old, new, pin):
+    text = open(_SRC).read()
+    assert text.count(old) == 1, f"mutation site not found: {name}"
+    path = oracle.build_copy(text.replace(old, new), str(tmp_path))
+    with oracle.use_library(path):
+        with pytest.raises(AssertionError):
+            pin()
