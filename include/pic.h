@@ -211,6 +211,20 @@ pic_status pic_init(const pic_config* cfg, const pic_buffers* bufs, void* hip_st
  * synchronizes. Errors: INVALID_ARG, CAPACITY. */
 pic_status pic_inject(pic_ctx* ctx, const pic_particles* src, int64_t* n_added);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): the Fowler-Nordheim
+ * emission of pic_inject(ctx, NULL, n_added), with the same result, whose
+ * work memory (the per-patch counts and per-block sums) is a static device
+ * array of 1 MiB held by each GPU the library runs on until the process ends,
+ * instead of the context's scratch. The caller still owns the particle
+ * arrays that receive the electrons. Allocates nothing. Every call on one GPU
+ * shares that GPU's array and leaves its contents behind (every entry a call
+ * reads is written earlier in the same call, so none needs clearing); calls
+ * that overlap on one GPU, from any context or stream, race. Errors:
+ * INVALID_ARG when the emission needs more than 1 MiB of work memory (about
+ * 260 000 patches), CAPACITY, STATE. Synchronizes the stream. */
+pic_status pic_inject_noalloc(pic_ctx* ctx, int64_t* n_added);
+
 /* Run nsteps steps of the phases selected in flags (PIC_STEP_*). The
  * work is enqueued on the stream; only the solve phase synchronizes (to test
  * convergence). */

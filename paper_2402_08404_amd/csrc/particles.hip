@@ -1551,7 +1551,12 @@ __global__ __launch_bounds__(kInjBlock) void k_inject(InjArgs a, Species<T> e) {
     }
 }
 
-hipError_t inject_phase(pic_ctx* c) {
+hipError_t inject_phase(pic_ctx* c) { return inject_phase_in(c, c->inj_cnt, c->inj_part); }
+
+// cnt: npatch uint32 counts; part: 2 doubles per count block. Every entry the
+// emission reads is written earlier in the same call, so neither needs
+// clearing.
+hipError_t inject_phase_in(pic_ctx* c, uint32_t* cnt, double* part) {
     InjArgs a;
     a.g = c->g;
     a.phi = c->buf.phi;
@@ -1569,8 +1574,8 @@ hipError_t inject_phase(pic_ctx* c) {
     a.st = c->st;
     a.cap = c->buf.cap[0];
     a.phi_w15 = pow(a.phi_w, 1.5);
-    a.cnt = c->inj_cnt;
-    a.part = c->inj_part;
+    a.cnt = cnt;
+    a.part = part;
     if (c->npatch == 0) return hipSuccess;
     const int64_t nb = (c->npatch + kInjCountBlock - 1) / kInjCountBlock;
     hipLaunchKernelGGL(k_inject_count, dim3((unsigned)nb), dim3(kInjCountBlock), 0, c->stream, a);

@@ -3,13 +3,43 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "pic_internal.hpp"
 
 using namespace pic;
 
+// Work memory of pic_inject_noalloc: a static device array, one copy per GPU
+// for the life of the process. In host code its name is not a device
+// address; the address of each device's copy is taken once per device with
+// hipGetSymbolAddress (static_work_setup, called by pic_init) and only that
+// address is used.
+constexpr size_t kStaticWorkBytes = (size_t)1 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticWorkBytes];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_addr[kMaxDevices] = {};
+
+// The address of the current device's copy of the static work array.
+hipError_t static_work_setup(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_static_addr[dev] = p;
+    }
+    *out = g_static_addr[dev];
+    return hipSuccess;
+}
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -274,6 +304,7 @@ pic_status pic_init(const pic_config* cfg, const pic_buffers* bufs, void* hip_st
     H(launch_zero(c->nflag, bufs->cap[2] * 4, c->stream), "zero");
     for (int k = 0; k < 2; ++k) H(launch_zero(c->bitmap[k], c->bm_words * 4, c->stream), "zero");
     H(launch_zero(bufs->rho, g.nn * 8, c->stream), "zero");
+    H(static_work_setup(&c->static_work), "static work array");
     H(launch_node_types(c), "node types");
     if (st == PIC_OK) {
         int r = mg_setup(c);
@@ -354,6 +385,30 @@ pic_status pic_inject(pic_ctx* c, const pic_particles* src, int64_t* n_added) {
     }
     unsigned long long before = c->host_st->injected;
     s = hip_check(c, inject_phase(c), "inject");
+    if (s != PIC_OK) return s;
+    s = sync_state(c);
+    if (s == PIC_OK && n_added) *n_added = (int64_t)(c->host_st->injected - before);
+    c->bins_valid = 0;
+    return s;
+}
+
+pic_status pic_inject_noalloc(pic_ctx* c, int64_t* n_added) {
+    if (!c) return PIC_E_INVALID_ARG;
+    if (c->failed) return PIC_E_STATE;
+    if (n_added) *n_added = 0;
+    const size_t need = inject_work_bytes(c->npatch);
+    if (need > kStaticWorkBytes)
+        return fail(c, PIC_E_INVALID_ARG,
+                    "emission of " + std::to_string(c->npatch) + " patches needs " + std::to_string(need) +
+                        " bytes of work memory, more than the " + std::to_string(kStaticWorkBytes) +
+                        "-byte static array of pic_inject_noalloc");
+    if (!c->static_work) return fail(c, PIC_E_STATE, "static work array not set up");
+    pic_status s = sync_state(c);
+    if (s != PIC_OK) return s;
+    unsigned long long before = c->host_st->injected;
+    uint32_t* cnt = (uint32_t*)c->static_work;
+    double* part = (double*)((char*)c->static_work + (((size_t)c->npatch * 4 + 255) & ~(size_t)255));
+    s = hip_check(c, inject_phase_in(c, cnt, part), "inject");
     if (s != PIC_OK) return s;
     s = sync_state(c);
     if (s == PIC_OK && n_added) *n_added = (int64_t)(c->host_st->injected - before);

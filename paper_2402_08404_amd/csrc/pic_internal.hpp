@@ -419,6 +419,7 @@ struct pic_ctx {
     int learn_smooth = 0;            // binomial filter passes on its output
     int learn_project = 1;           // weight the network output by the energy-norm projection
     int learn_fallback = 1;          // judge the learned guess against V0 phi1 before each solve
+    void* static_work = nullptr;     // this device's copy of the static work array (pic_inject_noalloc)
     double* phi_prev = nullptr;      // potential of the previous step solve (extrapolated guess)
     int phi_hist = 0;                // consecutive step solves whose potential phi_prev / phi hold
     // host state
@@ -468,6 +469,13 @@ hipError_t particles_phase(pic_ctx* c, bool move);
 hipError_t collide_phase(pic_ctx* c, bool record);
 hipError_t cell_bins(pic_ctx* c);
 hipError_t inject_phase(pic_ctx* c);
+// the emission with its per-patch counts and per-block sums in cnt and part
+hipError_t inject_phase_in(pic_ctx* c, uint32_t* cnt, double* part);
+// bytes of work memory of the emission (counts and block sums)
+inline size_t inject_work_bytes(int64_t npatch) {
+    const int64_t nb = (npatch + kInjCountBlock - 1) / kInjCountBlock;
+    return (((size_t)npatch * 4 + 255) & ~(size_t)255) + (size_t)nb * 16;
+}
 hipError_t load_particles(pic_ctx* c, const pic_particles* src);
 hipError_t moments_phase(pic_ctx* c, double* out_dev);
 hipError_t apex_interp(pic_ctx* c, const double* phi, double X, double Y, double Z, double* out_dev);

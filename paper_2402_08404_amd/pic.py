@@ -99,6 +99,7 @@ def lib():
         L.pic_scratch_size.argtypes = [C.POINTER(pic_config), C.POINTER(C.c_int64), C.POINTER(C.c_size_t)]
         L.pic_init.argtypes = [C.POINTER(pic_config), C.POINTER(pic_buffers), vp, C.POINTER(vp)]
         L.pic_inject.argtypes = [vp, C.POINTER(pic_particles), C.POINTER(C.c_int64)]
+        L.pic_inject_noalloc.argtypes = [vp, C.POINTER(C.c_int64)]
         L.pic_step.argtypes = [vp, C.c_int32, C.c_uint32]
         L.pic_solve_poisson.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_int32, C.POINTER(pic_solve_info)]
         L.pic_moments.argtypes = [vp, C.POINTER(pic_moments_t)]
@@ -124,7 +125,7 @@ def lib():
         L.unet_destroy.restype = None
         L.pic_set_learned_guess.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32]
         L.pic_training_sample.argtypes = [vp, vp, vp, C.POINTER(C.c_double)]
-        for f in ("pic_scratch_size", "pic_init", "pic_inject", "pic_step", "pic_solve_poisson", "pic_moments",
+        for f in ("pic_scratch_size", "pic_init", "pic_inject", "pic_inject_noalloc", "pic_step", "pic_solve_poisson", "pic_moments",
                   "pic_events", "unet_param_count", "unet_workspace_size", "unet_create", "unet_forward",
                   "unet_backward", "unet_adam_step", "unet_sync_params", "pic_set_learned_guess",
                   "pic_training_sample"):
@@ -158,6 +159,12 @@ def pic_init(cfg: pic_config, bufs: pic_buffers, stream: int):
 def pic_inject(ctx, src: pic_particles | None) -> int:
     n = C.c_int64()
     _check(lib().pic_inject(ctx, C.byref(src) if src is not None else None, C.byref(n)), ctx)
+    return n.value
+
+
+def pic_inject_noalloc(ctx) -> int:
+    n = C.c_int64()
+    _check(lib().pic_inject_noalloc(ctx, C.byref(n)), ctx)
     return n.value
 
 
