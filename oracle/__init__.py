@@ -149,6 +149,13 @@ def _load(path: str):
                               C.POINTER(C.c_uint32), C.POINTER(_CollideOut)]
     L.orc_collide.restype = C.c_int
     L.orc_moments.argtypes = [cfgp, C.POINTER(_Species), dp, dp]
+    L.orc_push_sr.argtypes = [cfgp, dp, C.c_void_p, C.POINTER(_Species), C.c_double, C.c_double,
+                              np.ctypeslib.ndpointer(np.int32, flags="C"), C.POINTER(C.c_double)]
+    L.orc_evap_flux.argtypes = [cfgp, C.c_double]
+    L.orc_evap_flux.restype = C.c_double
+    L.orc_evaporate.argtypes = [cfgp, C.c_uint32, C.c_double, C.POINTER(_Species), C.POINTER(C.c_uint32),
+                                C.POINTER(C.c_double)]
+    L.orc_evaporate.restype = C.c_int64
     return L
 
 
@@ -264,6 +271,13 @@ class Oracle:
         self.n_expected = 0.0
         self.fn_clamped = 0
         self.bsi_skips = 0
+        # surface and circuit terms (Sec. 2.3.1, Sec. 2.3.3)
+        self.V_gap = self.V0          # anode potential, the gap voltage of the RC circuit
+        self.i_gap = 0.0              # Shockley-Ramo current of the last push [A]
+        self.i_tot = 0.0              # circuit current of the last circuit step [A]
+        self.bomb_energy = np.zeros(2)  # kinetic energy of ions absorbed at the cathode plane and the tip [J]
+        self.evaporated = 0
+        self.evap_expected = 0.0
         self.last_events = []
         self.last_fragile = set()
         self.last_solve = (0, 0.0)
@@ -312,10 +326,11 @@ class Oracle:
         return self.Q
 
     def solve(self, rtol: float = 1e-8, maxit: int = 100000, guess: str = "previous"):
+        """Eq. poi with the anode at the gap voltage (V0 without the circuit)."""
         if guess == "zero":
             self.phi = np.zeros_like(self.phi)
         rr = C.c_double()
-        it = self.L.orc_solve(C.byref(self.c), self.type, self.Q, self.V0, self.phi, rtol, maxit, C.byref(rr))
+        it = self.L.orc_solve(C.byref(self.c), self.type, self.Q, self.V_gap, self.phi, rtol, maxit, C.byref(rr))
         self.last_solve = (it, rr.value)
         self.field()
         return it, rr.value
@@ -339,19 +354,65 @@ class Oracle:
         self.fn_clamped += ncl.value
         return k
 
+    def evaporate(self) -> int:
+        """Neutrals evaporated from the tip at the prescribed surface
+        temperature (Clausius-Clapeyron flux, Sec. 2.3.1)."""
+        if not self.cfg.surface_T > 0:
+            return 0
+        st = self.sp[SP_NEU]
+        flux = self.L.orc_evap_flux(C.byref(self.c), self.cfg.surface_T)
+        npatch = int(self.L.orc_fn_patch_count(C.byref(self.c)))
+        area = float(self.fn_patches()[:, 6].sum()) * self.cfg.h ** 2
+        st.ensure(int(flux * area * self.cfg.dt) + 8 * npatch + 64)
+        v = st.view()
+        nid = C.c_uint32(self.next_id)
+        nexp = C.c_double(0.0)
+        k = self.L.orc_evaporate(C.byref(self.c), self.step_no, self.cfg.surface_T, C.byref(v), C.byref(nid),
+                                 C.byref(nexp))
+        if k < 0:
+            raise RuntimeError("oracle: evaporation capacity")
+        st.n = int(v.n)
+        self.next_id = nid.value
+        self.evaporated += k
+        self.evap_expected += nexp.value
+        return k
+
     def push(self) -> list:
+        """Leapfrog push and removal (Sec. 2.2). Also: with the circuit on, the
+        Shockley-Ramo current of the pushed charges (kept in i_gap), and the kinetic energy
+        of the ions that end the step in the cathode plane or the tip (the
+        bombardment energy E_b of Sec. 2.3.3, sputtering left out so E_s = 0)."""
         codes = []
+        self.i_gap = 0.0
         for s in range(3):
             st = self.sp[s]
             code = np.zeros(max(st.n, 1), np.int32)
             v = st.view()
-            self.L.orc_push(C.byref(self.c), self.E, C.byref(v), self.charges[s], self.masses[s], code)
+            isr = C.c_double(0.0)
+            e0 = self.E0.ctypes.data_as(C.c_void_p) if self.cfg.circuit_R > 0 else None
+            self.L.orc_push_sr(C.byref(self.c), self.E, e0, C.byref(v), self.charges[s], self.masses[s], code,
+                               C.byref(isr))
+            self.i_gap += isr.value
             code = code[: st.n]
             for k in range(1, 5):
                 self.absorbed[s, k] += int((code == k).sum())
+            if s == SP_ION:
+                sv = self.cfg.h / self.cfg.dt
+                for j, k in ((0, CATHODE), (1, TIP)):
+                    m = code == k
+                    v2 = (st.a["vx"][: st.n][m] ** 2 + st.a["vy"][: st.n][m] ** 2 + st.a["vz"][: st.n][m] ** 2)
+                    self.bomb_energy[j] += float(np.sum(0.5 * self.masses[s] * v2 * sv * sv))
             st.keep(code == ALIVE)
             codes.append(code)
         return codes
+
+    def circuit_step(self, i_gap: float):
+        """The RC circuit of Sec. 2.3.1 advanced by one step (explicit Euler
+        of its integral): I_tot = (V0 - V_gap) / R, then
+        V_gap <- V_gap + dt / C (I_tot - I_gap)."""
+        cfg = self.cfg
+        self.i_tot = (self.V0 - self.V_gap) / cfg.circuit_R
+        self.V_gap = self.V_gap + cfg.dt / cfg.circuit_C * (self.i_tot - i_gap)
 
     def collide(self, flags: int = COLL_ALL):
         n_neu = self.sp[SP_NEU].n
@@ -380,7 +441,10 @@ class Oracle:
              solve: bool = True):
         if inject:
             self.inject()
+            self.evaporate()
         self.push()
+        if self.cfg.circuit_R > 0:
+            self.circuit_step(self.i_gap)
         if collide_flags:
             self.collide(collide_flags)
         self.deposit()
@@ -394,7 +458,9 @@ class Oracle:
         self.L.orc_moments(C.byref(self.c), arr, self.E0, out)
         return {"ke": out[0:3].copy(), "i_sr": float(out[3]), "n": out[4:7].astype(np.int64),
                 "q_total": int(self.Q.sum()), "absorbed": self.absorbed.copy(),
-                "events": self.events.copy(), "injected": self.injected}
+                "events": self.events.copy(), "injected": self.injected, "v_gap": self.V_gap,
+                "i_gap": self.i_gap, "i_tot": self.i_tot, "bomb_energy": self.bomb_energy.copy(),
+                "evaporated": self.evaporated, "evap_expected": self.evap_expected}
 
     # -- helpers for tests ----------------------------------------------------
     def gather(self, E: np.ndarray, X, Y, Z) -> np.ndarray:

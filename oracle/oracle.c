@@ -313,7 +313,19 @@ double orc_apex_field(const orc_config* c, const double* phi1) {
  * vacuum or anode boundary); code[] receives where each one left. */
 void orc_push(const orc_config* c, const double* E, orc_species* s, double q, double m,
               int32_t* code) {
+    orc_push_sr(c, E, NULL, s, q, m, code, NULL);
+}
+
+/* The push, also returning (E0 != NULL) the Shockley-Ramo current of the
+ * pushed particles (Sec. 2.3.1): I = sum q v . E0(r) over every particle of
+ * the species alive before the push, with the new velocity v^{n+1/2} and the
+ * weighting field E0 (the field of the unit-anode Laplace problem) at the
+ * position x^n where the kick's field was taken (reading: the paper does not
+ * fix the time level; v^{n+1/2} is the velocity of the step). */
+void orc_push_sr(const orc_config* c, const double* E, const double* E0, orc_species* s, double q, double m,
+                 int32_t* code, double* isr) {
     double h = c->h, dt = c->dt;
+    double sr = 0.0;
     for (int64_t p = 0; p < s->n; ++p) {
         if (q != 0.0) {
             double e[3];
@@ -323,6 +335,11 @@ void orc_push(const orc_config* c, const double* E, orc_species* s, double q, do
             vy += q / m * e[1] * dt;
             vz += q / m * e[2] * dt;
             s->vx[p] = vx * dt / h; s->vy[p] = vy * dt / h; s->vz[p] = vz * dt / h;
+            if (E0) {
+                double w[3];
+                orc_gather(c, E0, s->x[p], s->y[p], s->z[p], w);
+                sr += q * (vx * w[0] + vy * w[1] + vz * w[2]);
+            }
         }
         s->x[p] += s->vx[p];
         s->y[p] += s->vy[p];
@@ -335,6 +352,7 @@ void orc_push(const orc_config* c, const double* E, orc_species* s, double q, do
         else if (orc_inside_tip(c, X, Y, Z)) k = ORC_TIP;
         code[p] = k;
     }
+    if (isr) *isr = sr;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -486,6 +504,75 @@ int64_t orc_fn_inject(const orc_config* c, uint32_t step, const double* phi, orc
             e->z[m] = g[2] + 1e-3 * g[5];
             e->vx[m] = e->vy[m] = e->vz[m] = 0.0;
             e->id[m] = (*next_id)++;
+            ++added;
+        }
+    }
+    return added;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neutral evaporation from the tip surface (Sec. 2.3.1): the Clausius-
+ * Clapeyron flux
+ *   phi_vap = p_atm / sqrt(2 pi m k_B T) exp[(E_vap / k_B)(1/T_b - 1/T)]
+ * with p_atm = 101325 Pa, E_vap = 3.43 eV (the paper's value for Cu) and the
+ * boiling point T_b of Cu, 2835 K (not printed in the paper), at a prescribed
+ * uniform surface temperature T. Per emission patch N = phi_vap A dt atoms
+ * are expected; floor(N) plus one more with probability frac(N) are placed
+ * uniformly on the patch, 10^-3 spacings outside the surface. Reading of "speeds
+ * sampled from the Maxwell-Boltzmann distribution based on the surface
+ * temperature": the distribution of atoms leaving the surface at temperature
+ * T, i.e. a Rayleigh-distributed normal component (flux weighting of the
+ * Maxwellian) and Gaussian tangential components, each with variance
+ * k_B T / m. Draws: (patch, step, EVAP, 0) for the count; for atom j,
+ * (patch, step, EVAP, 1 + 3j) for the point, (.., 2 + 3j) and (.., 3 + 3j)
+ * for the velocity. Returns the number added, or -1 when capacity runs out. */
+#define TAG_EVAP 7u
+#define P_ATM 101325.0
+#define E_VAP_CU 3.43
+#define T_BOIL_CU 2835.0
+#define K_B 1.380649e-23
+
+double orc_evap_flux(const orc_config* c, double T) {
+    if (!(T > 0.0)) return 0.0;
+    return P_ATM / sqrt(2.0 * PI * c->m_ion * K_B * T) * exp(E_VAP_CU * E_CH / K_B * (1.0 / T_BOIL_CU - 1.0 / T));
+}
+
+int64_t orc_evaporate(const orc_config* c, uint32_t step, double T, orc_species* nsp, uint32_t* next_id,
+                      double* n_expected) {
+    int64_t np = orc_fn_patch_count(c), added = 0;
+    double h = c->h, flux = orc_evap_flux(c, T);
+    double sig = sqrt(K_B * T / c->m_ion) * c->dt / h;   /* grid units per step */
+    for (int64_t p = 0; p < np; ++p) {
+        double g[8];
+        orc_fn_patch(c, p, 0.5, 0.5, g);
+        double N = flux * g[6] * h * h * c->dt;
+        if (n_expected) *n_expected += N;
+        double u0, u1;
+        draw2(c, (uint32_t)p, step, TAG_EVAP, 0, &u0, &u1);
+        double fl = floor(N);
+        int64_t k = (int64_t)fl + ((u0 < N - fl) ? 1 : 0);
+        if (!grow_ok(nsp, k)) return -1;
+        for (int64_t j = 0; j < k; ++j) {
+            double ua, ub, w1, w2, w3, unused;
+            draw2(c, (uint32_t)p, step, TAG_EVAP, (uint32_t)(1 + 3 * j), &ua, &ub);
+            draw2(c, (uint32_t)p, step, TAG_EVAP, (uint32_t)(2 + 3 * j), &w1, &w2);
+            draw2(c, (uint32_t)p, step, TAG_EVAP, (uint32_t)(3 + 3 * j), &w3, &unused);
+            orc_fn_patch(c, p, ua, ub, g);
+            double n[3] = {g[3], g[4], g[5]};
+            double tl = sqrt(n[0] * n[0] + n[1] * n[1]);
+            double t1[3] = {-n[1] / tl, n[0] / tl, 0.0};
+            double t2[3] = {n[1] * t1[2] - n[2] * t1[1], n[2] * t1[0] - n[0] * t1[2], n[0] * t1[1] - n[1] * t1[0]};
+            double vn = sig * sqrt(-2.0 * log(w1));
+            double rt = sig * sqrt(-2.0 * log(w2));
+            double va = rt * cos(2.0 * PI * w3), vb = rt * sin(2.0 * PI * w3);
+            int64_t m = nsp->n++;
+            nsp->x[m] = g[0] + 1e-3 * n[0];
+            nsp->y[m] = g[1] + 1e-3 * n[1];
+            nsp->z[m] = g[2] + 1e-3 * n[2];
+            nsp->vx[m] = vn * n[0] + va * t1[0] + vb * t2[0];
+            nsp->vy[m] = vn * n[1] + va * t1[1] + vb * t2[1];
+            nsp->vz[m] = vn * n[2] + va * t1[2] + vb * t2[2];
+            nsp->id[m] = (*next_id)++;
             ++added;
         }
     }

@@ -78,6 +78,8 @@ double orc_apex_field(const orc_config* c, const double* phi1);
 
 void orc_push(const orc_config* c, const double* E, orc_species* s, double q, double m,
               int32_t* code);
+void orc_push_sr(const orc_config* c, const double* E, const double* E0, orc_species* s, double q, double m,
+                 int32_t* code, double* isr);
 void orc_deposit(const orc_config* c, const orc_species* s, int64_t sign, int64_t* Q);
 int64_t orc_cell_of(const orc_config* c, double X, double Y, double Z);
 
@@ -88,6 +90,10 @@ int64_t orc_fn_patch_count(const orc_config* c);
 void orc_fn_patch(const orc_config* c, int64_t p, double ua, double ub, double out[8]);
 int64_t orc_fn_inject(const orc_config* c, uint32_t step, const double* phi, orc_species* e,
                       uint32_t* next_id, double* n_expected, int64_t* n_clamped);
+
+double orc_evap_flux(const orc_config* c, double T);
+int64_t orc_evaporate(const orc_config* c, uint32_t step, double T, orc_species* nsp, uint32_t* next_id,
+                      double* n_expected);
 
 int orc_collide(const orc_config* c, uint32_t step, int32_t flags, const double* E,
                 orc_species* sp, uint32_t* next_id, orc_collide_out* out);

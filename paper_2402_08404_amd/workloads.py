@@ -54,6 +54,9 @@ class Config:
     xs_cx: np.ndarray = None
     fn_rings: int = 16
     fn_az: int = 64
+    surface_T: float = 0.0   # prescribed tip surface temperature for neutral evaporation [K] (0: none)
+    circuit_R: float = 0.0   # series resistance of the external RC circuit [ohm] (0: fixed anode potential)
+    circuit_C: float = 0.0   # gap capacitance of the RC circuit [F]
 
     @property
     def n_nodes(self) -> int:

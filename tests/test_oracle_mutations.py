@@ -8,6 +8,7 @@ import pytest
 
 import oracle
 import test_oracle_readings as R
+import test_oracle_surface as S
 
 _SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
 
@@ -45,6 +46,17 @@ MUTATIONS = [
      "g[0] + 0.5 * g[3], g[1] + 0.5 * g[4], g[2] + 0.5 * g[5]) / (0.5 * h);", R.pin_emission_field_point),
     ("emission field from the surface potential",
      "g[0] + g[3], g[1] + g[4], g[2] + g[5]) / h;", "g[0], g[1], g[2] + 1.0) / h;", R.pin_emission_field_point),
+    ("evaporation exponent with the wrong sign",
+     "(1.0 / T_BOIL_CU - 1.0 / T)", "(1.0 / T - 1.0 / T_BOIL_CU)", S.pin_evaporation_flux),
+    ("evaporation flux without the thermal prefactor's square root",
+     "P_ATM / sqrt(2.0 * PI * c->m_ion * K_B * T)", "P_ATM / (2.0 * PI * c->m_ion * K_B * T)",
+     S.pin_evaporation_flux),
+    ("half-Maxwellian instead of flux-weighted normal speeds",
+     "double vn = sig * sqrt(-2.0 * log(w1));",
+     "double vn = sig * fabs(sqrt(-2.0 * log(w1)) * cos(2.0 * PI * w2));", S.pin_evaporation_atoms),
+    ("Shockley-Ramo current from the field instead of the weighting field",
+     "orc_gather(c, E0, s->x[p], s->y[p], s->z[p], w);", "orc_gather(c, E, s->x[p], s->y[p], s->z[p], w);",
+     S.pin_shockley_ramo_push),
 ]
 
 
