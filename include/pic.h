@@ -71,8 +71,12 @@ typedef int32_t pic_status;
 #define PIC_GUESS_LEARNED 3   /* V0 phi1 plus the network's charge response (pic_set_learned_guess) */
 
 /* phases of pic_step; each step runs the selected phases in this order */
-#define PIC_STEP_INJECT 0x01   /* Fowler-Nordheim emission from the tip (Sec. 2.3.1) */
-#define PIC_STEP_PUSH 0x02     /* gather, leapfrog push, boundary removal, deposit, binning (Sec. 2.2) */
+#define PIC_STEP_INJECT 0x01   /* Fowler-Nordheim emission from the tip, then the evaporation of neutrals
+                                  when cfg.surface_T > 0 (Sec. 2.3.1) */
+#define PIC_STEP_PUSH 0x02     /* gather, leapfrog push, boundary removal, deposit, binning (Sec. 2.2);
+                                  the bombardment energy of ions reaching the cathode (Sec. 2.3.3); with the
+                                  circuit, the Shockley-Ramo current of the push and one step of the RC
+                                  circuit, whose gap voltage is the anode potential of the next solves */
 #define PIC_STEP_DEPOSIT 0x04  /* deposit and binning at the current positions, no motion */
 #define PIC_STEP_COLLIDE 0x08  /* MCC (Eqs. colp, du, newv), field ionization (Eq. dfi), products */
 #define PIC_STEP_SOLVE 0x10    /* Poisson solve (Eq. poi) from the previous potential (or its extrapolation, cfg.step_guess), then the field */
@@ -115,6 +119,11 @@ typedef struct pic_config {
     int32_t stencil_blocks; /* about this many blocks per z-marching solver kernel (0: 1024; 64..4096) */
     int32_t step_guess;    /* guess of the solve inside pic_step: 0 the previous potential, 1 linear
                               extrapolation 2 phi_n - phi_{n-1} from the two previous step solves */
+    /* Surface and circuit terms (Sec. 2.3.1): */
+    double surface_T;      /* prescribed uniform tip surface temperature [K] for the Clausius-Clapeyron
+                              evaporation of neutrals in the inject phase (0: no evaporation) */
+    double circuit_R;      /* series resistance [ohm] of the RC circuit (0: the anode stays at V0) */
+    double circuit_C;      /* gap capacitance [F] of the RC circuit */
 } pic_config;
 
 typedef struct pic_buffers {
@@ -176,6 +185,14 @@ typedef struct pic_moments_t {
     int32_t last_cg_iters;     /* iterations of the last Poisson solve */
     double last_cg_relres;     /* final relative residual of the last solve */
     int64_t cg_iters_total;    /* iterations of all solves since pic_init (the init solve excluded) */
+    /* surface and circuit terms */
+    int64_t evaporated;        /* cumulative evaporated neutrals */
+    double evap_expected;      /* cumulative expected number of evaporated neutrals */
+    double bomb_energy[2];     /* cumulative kinetic energy [J] of ions absorbed at the cathode plane and the tip
+                                  (the bombardment energy E_b of Sec. 2.3.3; no sputtering, E_s = 0) */
+    double v_gap;              /* gap voltage = anode potential [V] (V0 without the circuit) */
+    double i_gap;              /* Shockley-Ramo current of the last push [A] (circuit only) */
+    double i_tot;              /* circuit current (V0 - V_gap) / R of the last circuit step [A] */
 } pic_moments_t;
 
 typedef struct pic_event {
@@ -206,9 +223,10 @@ pic_status pic_init(const pic_config* cfg, const pic_buffers* bufs, void* hip_st
 
 /* With src != NULL: append src->n particles of one species (copied from
  * device memory), numbering them from the next id in array order.
- * With src == NULL: Fowler-Nordheim emission for the current step (as
- * PIC_STEP_INJECT). n_added (optional) receives the number appended; the call
- * synchronizes. Errors: INVALID_ARG, CAPACITY. */
+ * With src == NULL: the surface injection of the current step (as
+ * PIC_STEP_INJECT): Fowler-Nordheim emission, then evaporation when
+ * cfg.surface_T > 0. n_added (optional) receives the number appended; the
+ * call synchronizes. Errors: INVALID_ARG, CAPACITY. */
 pic_status pic_inject(pic_ctx* ctx, const pic_particles* src, int64_t* n_added);
 
 /* For callers that cannot allocate device memory (code under stream capture,

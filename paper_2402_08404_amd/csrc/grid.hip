@@ -257,6 +257,7 @@ struct CgArgs {
     const int64_t* rho;
     double qscale;   // 2^-40 e / (eps0 h)
     double V0;
+    const double* V0_dev;   // when set, the anode value (the circuit's gap voltage) is read here
     DevState* s;
     double* part_pq;  // kCgBlocks partials of p.q
     double* part_rr;  // kCgBlocks partials of r.r
@@ -288,7 +289,7 @@ __global__ void k_cg_init(CgArgs a, int zero_guess) {
     if (n >= g.nn) return;
     uint8_t t = a.type[n];
     if (t != 0) {
-        a.x[n] = (t == 2) ? a.V0 : 0.0;
+        a.x[n] = (t == 2) ? (a.V0_dev ? *a.V0_dev : a.V0) : 0.0;
         a.r[n] = 0.0;
     } else if (zero_guess) {
         a.x[n] = 0.0;
@@ -543,6 +544,7 @@ int cg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess, 
     a.rho = rho;
     a.qscale = ldexp(1.0, -40) * kQe / (kEps0 * g.h);
     a.V0 = V0;
+    a.V0_dev = (c->circuit && phi == c->buf.phi) ? &c->st->v_gap : nullptr;
     a.s = c->st;
     a.part_pq = c->partials;
     a.part_rr = c->partials + kCgBlocks;
@@ -906,6 +908,7 @@ int mgcg_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int guess
     a.rho = rho;
     a.qscale = ldexp(1.0, -40) * kQe / (kEps0 * g.h);
     a.V0 = V0;
+    a.V0_dev = (c->circuit && phi == c->buf.phi) ? &c->st->v_gap : nullptr;
     a.s = c->st;
     a.part_pq = c->partials + kPartPq;
     a.part_rr = c->partials + kPartRr;
@@ -994,6 +997,7 @@ int mixed_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int gues
     a.rho = rho;
     a.qscale = ldexp(1.0, -40) * kQe / (kEps0 * g.h);
     a.V0 = V0;
+    a.V0_dev = (c->circuit && phi == c->buf.phi) ? &c->st->v_gap : nullptr;
     a.s = c->st;
     a.part_pq = c->partials + kPartPq;
     a.part_rr = c->partials + kPartRr;

@@ -39,6 +39,9 @@ struct PushArgs {
     uint64_t seed;
     uint32_t* fi_list;
     uint32_t* part;  // per-block partials: [block][8] = max speed bits, lost[1..4], bsi
+    double* dpart;   // per-block FP64 partials: [block][4] = sum |V|^2 of ions reaching the cathode plane and
+                     // the tip, sum V . E0 (the Shockley-Ramo current before its factor)
+    const typename V4<T>::type* field0;  // weighting field (with the circuit only, else null)
     double fi_thr, ebsi, adk_c, adk_e, x32, dt_fs;
 };
 
@@ -80,6 +83,10 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs<T> a) {
     // counted per thread, reduced per block (one atomic per block and kind)
     unsigned int lost[5] = {0, 0, 0, 0, 0};
     unsigned int bsi = 0;
+    // ions reaching the cathode plane and the tip (bombardment, Sec. 2.3.3)
+    // and the Shockley-Ramo sum of the pushed charges (Sec. 2.3.1)
+    double bomb[2] = {0.0, 0.0};
+    double sr = 0.0;
     // Every wavefront runs the loop the same number of times (lanes past the
     // last slot load the last slot and store nothing), so that all lanes take
     // part in the count of the keys.
@@ -102,6 +109,12 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs<T> a) {
                 VX += a.kq * ex;
                 VY += a.kq * ey;
                 VZ += a.kq * ez;
+                if (a.field0) {
+                    // the weighting field at x^n with v^{n+1/2}
+                    T wx, wy, wz;
+                    gather<T>(g, a.field0, X, Y, Z, wx, wy, wz);
+                    if (alive) sr += (double)VX * (double)wx + (double)VY * (double)wy + (double)VZ * (double)wz;
+                }
             }
             X += VX;
             Y += VY;
@@ -133,6 +146,10 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs<T> a) {
         if (code != 0) {
             a.s.id[i] = kDead;
             lost[code]++;
+            if (SP == PIC_ION && MOVE && (code == 1 || code == 4)) {
+                const double vx = (double)VX, vy = (double)VY, vz = (double)VZ;
+                bomb[code == 1 ? 0 : 1] += vx * vx + vy * vy + vz * vz;
+            }
             continue;
         }
         double vx = (double)VX, vy = (double)VY, vz = (double)VZ;
@@ -180,6 +197,20 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs<T> a) {
         for (int k = 1; k < 5; ++k) q[k] = tl[k];
         q[5] = tb;
     }
+    if ((SP == PIC_ION && MOVE) || (SP != PIC_NEUTRAL && MOVE && a.field0)) {
+        __shared__ double shd[kBlock / 64];
+        const double b0 = block_sum(bomb[0], shd);
+        __syncthreads();
+        const double b1 = block_sum(bomb[1], shd);
+        __syncthreads();
+        const double s0 = block_sum(sr, shd);
+        if (threadIdx.x == 0) {
+            double* q = a.dpart + (int64_t)blockIdx.x * 4;
+            q[0] = b0;
+            q[1] = b1;
+            q[2] = s0;
+        }
+    }
 }
 
 // Reduction of the push partials of one species (one block of 1024
@@ -187,8 +218,13 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs<T> a) {
 // and a maximum, so the order does not matter).
 constexpr int kFinalBlock = 1024;
 
+// With dpart (moving ions, or charges with the circuit): the FP64 partials,
+// each thread adding its blocks in order, then a fixed-order block sum:
+// bomb_scale = m / 2 (h/dt)^2 turns sum |V|^2 into joules, sr_scale = q h/dt
+// turns sum V . E0 into amperes.
 template <int SP>
-__global__ __launch_bounds__(kFinalBlock) void k_push_final(DevState* st, const uint32_t* part, int nblocks) {
+__global__ __launch_bounds__(kFinalBlock) void k_push_final(DevState* st, const uint32_t* part, int nblocks,
+                                                            const double* dpart, double bomb_scale, double sr_scale) {
     __shared__ unsigned long long sh[kFinalBlock / 64];
     __shared__ unsigned int shm[kFinalBlock / 64];
     unsigned int m = 0;
@@ -228,6 +264,35 @@ __global__ __launch_bounds__(kFinalBlock) void k_push_final(DevState* st, const 
         for (int k = 1; k < 5; ++k) st->absorbed[SP][k] += t[k];
         st->bsi_count += t[5];
     }
+    if (dpart) {
+        __shared__ double shd[kFinalBlock / 64];
+        double d[3] = {0.0, 0.0, 0.0};
+        for (int b = (int)threadIdx.x; b < nblocks; b += kFinalBlock)
+            for (int k = 0; k < 3; ++k) d[k] += dpart[(int64_t)b * 4 + k];
+        double r[3];
+        for (int k = 0; k < 3; ++k) {
+            r[k] = block_sum(d[k], shd);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) {
+            if (SP == PIC_ION) {
+                st->bomb_e[0] += bomb_scale * r[0];
+                st->bomb_e[1] += bomb_scale * r[1];
+            }
+            if (SP != PIC_NEUTRAL) st->isr[SP] = sr_scale * r[2];
+        }
+    }
+}
+
+// One step of the RC circuit (Sec. 2.3.1), explicit in time: I_tot = (V0 -
+// V_gap) / R, V_gap += dt / C (I_tot - I_gap) with I_gap the Shockley-Ramo
+// current of this step's push. The next solves hold the anode at V_gap.
+__global__ void k_circuit(DevState* st, double V0, double R, double C, double dt) {
+    const double ig = st->isr[0] + st->isr[1];
+    const double it = (V0 - st->v_gap) / R;
+    st->i_gap = ig;
+    st->i_tot = it;
+    st->v_gap = st->v_gap + dt / C * (it - ig);
 }
 
 // ---------------------------------------------------------------------------
@@ -1174,6 +1239,8 @@ static hipError_t particles_t(pic_ctx* c, bool move) {
         a.seed = cf.seed;
         a.fi_list = c->fi_list;
         a.part = c->push_part;
+        a.dpart = c->push_dpart;
+        a.field0 = (move && c->circuit && s != PIC_NEUTRAL) ? (const typename V4<T>::type*)c->buf.field0 : nullptr;
         a.fi_thr = c->fi_thr;
         a.ebsi = c->ebsi;
         a.adk_c = c->adk_c;
@@ -1193,15 +1260,23 @@ static hipError_t particles_t(pic_ctx* c, bool move) {
             if (s == 2) hipLaunchKernelGGL((k_push<T, 2, false>), dim3(G), dim3(kBlock), 0, c->stream, a);
         }
         toc(c, t_e);
+        // the FP64 partials exist for moving ions (bombardment) and, with the
+        // circuit, for moving charges (Shockley-Ramo current)
+        const double sv = cf.h / cf.dt;
+        const double* dp = (move && (s == PIC_ION || (s == PIC_ELECTRON && c->circuit))) ? c->push_dpart : nullptr;
+        const double bsc = 0.5 * cf.m_ion * sv * sv;
+        const double ssc = (s == PIC_ELECTRON ? -kQe : kQe) * sv;
         if (s == 0) hipLaunchKernelGGL(k_push_final<0>, dim3(1), dim3(kFinalBlock), 0, c->stream, c->st,
-                                       (const uint32_t*)a.part, (int)G);
+                                       (const uint32_t*)a.part, (int)G, dp, bsc, ssc);
         if (s == 1) hipLaunchKernelGGL(k_push_final<1>, dim3(1), dim3(kFinalBlock), 0, c->stream, c->st,
-                                       (const uint32_t*)a.part, (int)G);
+                                       (const uint32_t*)a.part, (int)G, dp, bsc, ssc);
         if (s == 2) hipLaunchKernelGGL(k_push_final<2>, dim3(1), dim3(kFinalBlock), 0, c->stream, c->st,
-                                       (const uint32_t*)a.part, (int)G);
+                                       (const uint32_t*)a.part, (int)G, (const double*)nullptr, bsc, ssc);
         if (s == 2) toc(c, c->push_all_handle);
         if (s == 0) c->push_all_handle = t_all;
     }
+    if (move && c->circuit)
+        hipLaunchKernelGGL(k_circuit, dim3(1), dim3(1), 0, c->stream, c->st, c->V0, cf.circuit_R, cf.circuit_C, cf.dt);
     return bin_t<T>(c);
 }
 
@@ -1320,11 +1395,16 @@ hipError_t collide_phase(pic_ctx* c, bool record) {
 }
 
 // ---------------------------------------------------------------------------
-// Field emission (Sec. 2.3.1): per patch of the analytic tip surface, the
-// field one spacing out along the normal gives the Murphy-Good current
-// density J; N = J A dt / e electrons are expected, floor(N) are injected
-// plus one with probability frac(N), uniformly on the patch, 10^-3 spacings
-// outside the surface, at rest. Ids follow patch order.
+// Surface injection (Sec. 2.3.1), per patch of the analytic tip surface;
+// floor(N) particles plus one with probability frac(N) are placed uniformly
+// on the patch, 10^-3 spacings outside the surface; ids follow patch order.
+//  - Field emission (kind 0): the field one spacing out along the normal
+//    gives the Murphy-Good current density J, N = J A dt / e electrons, at
+//    rest.
+//  - Evaporation (kind 1): the Clausius-Clapeyron flux at the prescribed
+//    surface temperature (taken on the host) gives N = flux A dt neutrals,
+//    leaving with a Rayleigh-distributed normal speed and Gaussian tangential
+//    components (the Maxwellian of the surface temperature, flux weighted).
 
 struct InjArgs {
     Grid g;
@@ -1339,6 +1419,9 @@ struct InjArgs {
     double phi_w15;    // phi_w^1.5, taken on the host
     uint32_t* cnt;     // count of each patch
     double* part;      // per count block: expected count, clamped patches
+    int kind;          // 0 field emission (electrons), 1 evaporation (neutrals)
+    double evap_flux;  // evaporation flux [1/(m^2 s)]
+    double vsig;       // evaporation: sqrt(k_B T / m) in grid units per step
 };
 
 __device__ inline double interp_phi(const Grid& g, const double* phi, double X, double Y, double Z) {
@@ -1388,9 +1471,16 @@ __device__ inline void patch_point(const InjArgs& a, int64_t p, double ua, doubl
 __device__ inline int64_t patch_count(const InjArgs& a, int64_t p, double* nexp, int* clamped) {
     double q[7];
     patch_point(a, p, 0.5, 0.5, q);
+    *clamped = 0;
+    if (a.kind == 1) {
+        const double N = a.evap_flux * q[6] * a.h * a.h * a.dt;
+        *nexp = N;
+        Draw2 u = draw2(a.seed, (uint32_t)p, a.step, kTagEvap, 0);
+        double fl = floor(N);
+        return (int64_t)fl + ((u.a < N - fl) ? 1 : 0);
+    }
     double F = interp_phi(a.g, a.phi, q[0] + q[3], q[1] + q[4], q[2] + q[5]) / a.h;
     double J = 0.0;
-    *clamped = 0;
     if (F > 0.0) {
         double f = a.fn_cs2 * F / (a.phi_w * a.phi_w);
         if (f > 1.0) {
@@ -1471,7 +1561,8 @@ __global__ __launch_bounds__(kInjBlock) void k_inject(InjArgs a, Species<T> e) {
     __shared__ int64_t wsum[kInjBlock / 64];
     __shared__ double shd[kInjBlock / 64];
     const int t = threadIdx.x;
-    const int64_t base = (int64_t)a.st->n_slots[PIC_ELECTRON];
+    const int sp = a.kind == 0 ? PIC_ELECTRON : PIC_NEUTRAL;
+    const int64_t base = (int64_t)a.st->n_slots[sp];
     const uint32_t id0 = (uint32_t)a.st->next_id;
     int64_t carry = 0;
     bool over = false;
@@ -1513,16 +1604,36 @@ __global__ __launch_bounds__(kInjBlock) void k_inject(InjArgs a, Species<T> e) {
                 for (int s = kInjChunk / 2; s > 0; s >>= 1)
                     if ((int64_t)poff[lo + s] <= q) lo += s;
                 const int64_t p = c0 + lo, j = q - (int64_t)poff[lo];
-                Draw2 d = draw2(a.seed, (uint32_t)p, a.step, kTagInj, (uint32_t)(1 + j));
-                double pt[7];
-                patch_point(a, p, d.a, d.b, pt);
                 const int64_t m = base + carry + q;
+                double pt[7];
+                if (a.kind == 0) {
+                    Draw2 d = draw2(a.seed, (uint32_t)p, a.step, kTagInj, (uint32_t)(1 + j));
+                    patch_point(a, p, d.a, d.b, pt);
+                    e.vx[m] = (T)0;
+                    e.vy[m] = (T)0;
+                    e.vz[m] = (T)0;
+                } else {
+                    Draw2 d = draw2(a.seed, (uint32_t)p, a.step, kTagEvap, (uint32_t)(1 + 3 * j));
+                    Draw2 w12 = draw2(a.seed, (uint32_t)p, a.step, kTagEvap, (uint32_t)(2 + 3 * j));
+                    Draw2 w3 = draw2(a.seed, (uint32_t)p, a.step, kTagEvap, (uint32_t)(3 + 3 * j));
+                    patch_point(a, p, d.a, d.b, pt);
+                    // outward normal n and the tangents t1 = (-n_y, n_x, 0) / |.|, t2 = n x t1
+                    const double n0 = pt[3], n1 = pt[4], n2 = pt[5];
+                    const double tl = sqrt(n0 * n0 + n1 * n1);
+                    const double t10 = -n1 / tl, t11 = n0 / tl, t12 = 0.0;
+                    const double t20 = n1 * t12 - n2 * t11, t21 = n2 * t10 - n0 * t12, t22 = n0 * t11 - n1 * t10;
+                    const double vn = a.vsig * sqrt(-2.0 * log(w12.a));
+                    const double rt = a.vsig * sqrt(-2.0 * log(w12.b));
+                    double sn, cs;
+                    sincos(2.0 * kPi * w3.a, &sn, &cs);
+                    const double va = rt * cs, vb = rt * sn;
+                    e.vx[m] = (T)(vn * n0 + va * t10 + vb * t20);
+                    e.vy[m] = (T)(vn * n1 + va * t11 + vb * t21);
+                    e.vz[m] = (T)(vn * n2 + va * t12 + vb * t22);
+                }
                 e.x[m] = (T)(pt[0] + 1e-3 * pt[3]);
                 e.y[m] = (T)(pt[1] + 1e-3 * pt[4]);
                 e.z[m] = (T)(pt[2] + 1e-3 * pt[5]);
-                e.vx[m] = (T)0;
-                e.vy[m] = (T)0;
-                e.vz[m] = (T)0;
                 e.id[m] = id0 + (uint32_t)(carry + q);
             }
         }
@@ -1539,14 +1650,19 @@ __global__ __launch_bounds__(kInjBlock) void k_inject(InjArgs a, Species<T> e) {
     const double NE = block_sum(ne, shd);
     const double CL = block_sum(cl, shd);
     if (t == 0) {
-        a.st->fn_expected += NE;
-        a.st->fn_clamped += (unsigned long long)CL;
+        if (a.kind == 0) {
+            a.st->fn_expected += NE;
+            a.st->fn_clamped += (unsigned long long)CL;
+        } else {
+            a.st->evap_expected += NE;
+        }
         if (over) {
             atomicCAS(&a.st->error, 0, PIC_E_CAPACITY);
         } else {
-            a.st->n_slots[PIC_ELECTRON] += (unsigned long long)carry;
+            a.st->n_slots[sp] += (unsigned long long)carry;
             a.st->next_id += (unsigned long long)carry;
-            a.st->injected += (unsigned long long)carry;
+            if (a.kind == 0) a.st->injected += (unsigned long long)carry;
+            else a.st->evaporated += (unsigned long long)carry;
         }
     }
 }
@@ -1576,13 +1692,27 @@ hipError_t inject_phase_in(pic_ctx* c, uint32_t* cnt, double* part) {
     a.phi_w15 = pow(a.phi_w, 1.5);
     a.cnt = cnt;
     a.part = part;
+    a.kind = 0;
+    a.evap_flux = 0.0;
+    a.vsig = 0.0;
     if (c->npatch == 0) return hipSuccess;
     const int64_t nb = (c->npatch + kInjCountBlock - 1) / kInjCountBlock;
-    hipLaunchKernelGGL(k_inject_count, dim3((unsigned)nb), dim3(kInjCountBlock), 0, c->stream, a);
-    if (c->cfg.precision == PIC_F32)
-        hipLaunchKernelGGL(k_inject<float>, dim3(1), dim3(kInjBlock), 0, c->stream, a, species<float>(c, 0));
-    else
-        hipLaunchKernelGGL(k_inject<double>, dim3(1), dim3(kInjBlock), 0, c->stream, a, species<double>(c, 0));
+    // field emission, then (same work memory, in stream order) evaporation
+    for (int kind = 0; kind < 2; ++kind) {
+        if (kind == 1) {
+            if (!(c->cfg.surface_T > 0.0)) break;
+            a.kind = 1;
+            a.evap_flux = c->evap_flux;
+            a.vsig = c->evap_vsig;
+            a.cap = c->buf.cap[PIC_NEUTRAL];
+        }
+        const int sp = kind == 0 ? PIC_ELECTRON : PIC_NEUTRAL;
+        hipLaunchKernelGGL(k_inject_count, dim3((unsigned)nb), dim3(kInjCountBlock), 0, c->stream, a);
+        if (c->cfg.precision == PIC_F32)
+            hipLaunchKernelGGL(k_inject<float>, dim3(1), dim3(kInjBlock), 0, c->stream, a, species<float>(c, sp));
+        else
+            hipLaunchKernelGGL(k_inject<double>, dim3(1), dim3(kInjBlock), 0, c->stream, a, species<double>(c, sp));
+    }
     return hipGetLastError();
 }
 

@@ -85,6 +85,11 @@ const char* check_config(const pic_config* cfg) {
         return "stencil_blocks must be 0 or in 64..4096";
     if (cfg->step_guess < 0 || cfg->step_guess > 1) return "step_guess must be 0 or 1";
     if (cfg->id_capacity < 0 || cfg->id_capacity > ((int64_t)1 << 32)) return "id_capacity out of range";
+    if (!(cfg->surface_T >= 0.0) || !std::isfinite(cfg->surface_T)) return "surface_T must be finite and >= 0";
+    if (!(cfg->circuit_R >= 0.0) || !std::isfinite(cfg->circuit_R)) return "circuit_R must be finite and >= 0";
+    if (cfg->circuit_R > 0.0 && !(cfg->circuit_C > 0.0 && std::isfinite(cfg->circuit_C)))
+        return "the circuit needs circuit_C > 0";
+    if (cfg->surface_T > 0.0 && cfg->fn_rings == 0) return "evaporation needs the surface patches (fn_rings, fn_az)";
     return nullptr;
 }
 
@@ -101,6 +106,17 @@ __global__ void k_scale(double* y, const double* x, double a, int64_t n) {
 
 __global__ void k_init_state(DevState* st) {
     memset(st, 0, sizeof(DevState));
+}
+
+__global__ void k_set_vgap(DevState* st, double v) { st->v_gap = v; }
+
+// Clausius-Clapeyron evaporation flux [1/(m^2 s)] of Cu at T (Sec. 2.3.1):
+// p_atm / sqrt(2 pi m k_B T) exp[(E_vap / k_B)(1/T_b - 1/T)], E_vap = 3.43 eV,
+// T_b = 2835 K (the boiling point of Cu), p_atm = 101325 Pa.
+double evaporation_flux(double m, double T) {
+    const double kB = 1.380649e-23, p_atm = 101325.0, e_vap = 3.43, t_boil = 2835.0;
+    if (!(T > 0.0)) return 0.0;
+    return p_atm / std::sqrt(2.0 * kPi * m * kB * T) * std::exp(e_vap * kQe / kB * (1.0 / t_boil - 1.0 / T));
 }
 
 }  // namespace
@@ -139,6 +155,7 @@ size_t pic::scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[
     t->mcc_dense = (uint32_t*)take(nc * 4);
     t->fi_list = (uint32_t*)take(cap[2] * 4);
     t->push_part = (uint32_t*)take(8192 * 8 * 4);
+    t->push_dpart = (double*)take(8192 * 4 * 8);
     const int64_t npatch = fn_patches(cfg);
     t->inj_cnt = (uint32_t*)take(std::max<int64_t>(npatch, 1) * 4);
     t->inj_part = (double*)take(2 * std::max<int64_t>((npatch + kInjCountBlock - 1) / kInjCountBlock, 1) * 8);
@@ -280,6 +297,8 @@ pic_status pic_init(const pic_config* cfg, const pic_buffers* bufs, void* hip_st
         }
     }
     c->npatch = fn_patches(cfg);
+    c->evap_flux = evaporation_flux(cfg->m_ion, cfg->surface_T);
+    c->evap_vsig = std::sqrt(1.380649e-23 * cfg->surface_T / cfg->m_ion) * cfg->dt / cfg->h;
 
     pic_status st = PIC_OK;
     auto H = [&](hipError_t e, const char* w) {
@@ -332,6 +351,11 @@ pic_status pic_init(const pic_config* cfg, const pic_buffers* bufs, void* hip_st
         int64_t G = (g.nn + kBlock - 1) / kBlock;
         hipLaunchKernelGGL(k_scale, dim3((unsigned)G), dim3(kBlock), 0, c->stream, bufs->phi, bufs->phi1, c->V0, g.nn);
         H(launch_field(c, bufs->phi, bufs->field), "field");
+        // the gap voltage starts at the applied voltage; from now on, with
+        // the circuit, the solves hold the anode at it (after the unit-anode
+        // Laplace solve above, which must not)
+        hipLaunchKernelGGL(k_set_vgap, dim3(1), dim3(1), 0, c->stream, c->st, c->V0);
+        c->circuit = cfg->circuit_R > 0.0;
         H(hipStreamSynchronize(c->stream), "sync");
     }
     if (st != PIC_OK) {
@@ -595,6 +619,13 @@ pic_status pic_moments(pic_ctx* c, pic_moments_t* out) {
     out->last_cg_iters = c->last_solve.iterations;
     out->last_cg_relres = c->last_solve.relres;
     out->cg_iters_total = c->cg_iters_total;
+    out->evaporated = (int64_t)h->evaporated;
+    out->evap_expected = h->evap_expected;
+    out->bomb_energy[0] = h->bomb_e[0];
+    out->bomb_energy[1] = h->bomb_e[1];
+    out->v_gap = h->v_gap;
+    out->i_gap = h->i_gap;
+    out->i_tot = h->i_tot;
     return s;
 }
 

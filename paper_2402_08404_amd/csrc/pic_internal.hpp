@@ -29,7 +29,7 @@ constexpr int kBigCell = 4096;                // cells up to this many: one wave
 constexpr int kBlock = 256;
 
 // Third Philox counter word: purpose of the draw.
-constexpr uint32_t kTagMcc1 = 1, kTagMcc2 = 2, kTagPair1 = 3, kTagPair2 = 4, kTagFi = 5, kTagInj = 6;
+constexpr uint32_t kTagMcc1 = 1, kTagMcc2 = 2, kTagPair1 = 3, kTagPair2 = 4, kTagFi = 5, kTagInj = 6, kTagEvap = 7;
 
 // Device-resident counters and scalars of one context.
 struct DevState {
@@ -57,6 +57,12 @@ struct DevState {
     double learn_scale;
     double learn_gamma;
     int learn_bad;                     // the network output of the last learned guess was not finite
+    // surface and circuit terms
+    unsigned long long evaporated;
+    double evap_expected;
+    double bomb_e[2];                  // kinetic energy of ions absorbed at the cathode plane / the tip [J]
+    double isr[2];                     // Shockley-Ramo current of the last push, electrons and ions [A]
+    double v_gap, i_gap, i_tot;        // RC circuit: gap voltage (anode potential), currents [V, A]
 };
 
 // Cells are numbered tile-major: tiles of kTile^3 cells, tile index
@@ -420,6 +426,10 @@ struct pic_ctx {
     int learn_project = 1;           // weight the network output by the energy-norm projection
     int learn_fallback = 1;          // judge the learned guess against V0 phi1 before each solve
     void* static_work = nullptr;     // this device's copy of the static work array (pic_inject_noalloc)
+    double* push_dpart = nullptr;    // per-block FP64 partials of the push kernels (8192 x 4)
+    bool circuit = false;            // cfg.circuit_R > 0: the anode follows the RC circuit
+    double evap_flux = 0.0;          // Clausius-Clapeyron flux at cfg.surface_T [1/(m^2 s)]
+    double evap_vsig = 0.0;          // sqrt(k_B T / m) dt / h
     double* phi_prev = nullptr;      // potential of the previous step solve (extrapolated guess)
     int phi_hist = 0;                // consecutive step solves whose potential phi_prev / phi hold
     // host state

@@ -47,7 +47,8 @@ class pic_config(C.Structure):
                 ("xs_el", C.POINTER(C.c_double)), ("xs_iz", C.POINTER(C.c_double)), ("xs_cx", C.POINTER(C.c_double)),
                 ("fn_rings", C.c_int32), ("fn_az", C.c_int32), ("laplace_rtol", C.c_double),
                 ("step_rtol", C.c_double), ("step_maxit", C.c_int32), ("sort_every", C.c_int32),
-                ("id_capacity", C.c_int64), ("stencil_blocks", C.c_int32), ("step_guess", C.c_int32)]
+                ("id_capacity", C.c_int64), ("stencil_blocks", C.c_int32), ("step_guess", C.c_int32),
+                ("surface_T", C.c_double), ("circuit_R", C.c_double), ("circuit_C", C.c_double)]
 
 
 class pic_buffers(C.Structure):
@@ -73,7 +74,9 @@ class pic_moments_t(C.Structure):
                 ("bsi_count", C.c_int64), ("q_total", C.c_int64), ("next_id", C.c_int64), ("step", C.c_int64),
                 ("ke", C.c_double * 3), ("i_sr", C.c_double), ("fn_expected", C.c_double), ("v0", C.c_double),
                 ("apex_field1", C.c_double), ("error", C.c_int32), ("last_cg_iters", C.c_int32),
-                ("last_cg_relres", C.c_double), ("cg_iters_total", C.c_int64)]
+                ("last_cg_relres", C.c_double), ("cg_iters_total", C.c_int64),
+                ("evaporated", C.c_int64), ("evap_expected", C.c_double), ("bomb_energy", C.c_double * 2),
+                ("v_gap", C.c_double), ("i_gap", C.c_double), ("i_tot", C.c_double)]
 
 
 class pic_unet_config(C.Structure):
@@ -192,7 +195,9 @@ def pic_moments(ctx) -> dict:
             "injected": m.injected, "fn_clamped": m.fn_clamped, "bsi_count": m.bsi_count, "q_total": m.q_total,
             "next_id": m.next_id, "step": m.step, "ke": np.array(m.ke[:]), "i_sr": m.i_sr,
             "fn_expected": m.fn_expected, "v0": m.v0, "apex_field1": m.apex_field1, "error": m.error,
-            "last_cg_iters": m.last_cg_iters, "last_cg_relres": m.last_cg_relres, "cg_iters_total": m.cg_iters_total}
+            "last_cg_iters": m.last_cg_iters, "last_cg_relres": m.last_cg_relres, "cg_iters_total": m.cg_iters_total,
+            "evaporated": m.evaporated, "evap_expected": m.evap_expected, "bomb_energy": np.array(m.bomb_energy[:]),
+            "v_gap": m.v_gap, "i_gap": m.i_gap, "i_tot": m.i_tot}
 
 
 def pic_events(ctx, cap: int) -> list:
@@ -296,7 +301,9 @@ def make_config(cfg: workloads.Config, precision=PIC_F64, solver=PIC_SOLVER_CG, 
                    xs_emax=cfg.xs_emax, xs_el=keep[0].ctypes.data_as(dp), xs_iz=keep[1].ctypes.data_as(dp),
                    xs_cx=keep[2].ctypes.data_as(dp), fn_rings=cfg.fn_rings, fn_az=cfg.fn_az,
                    laplace_rtol=laplace_rtol, step_rtol=step_rtol, step_maxit=step_maxit, sort_every=sort_every,
-                   id_capacity=id_capacity, stencil_blocks=stencil_blocks, step_guess=step_guess)
+                   id_capacity=id_capacity, stencil_blocks=stencil_blocks, step_guess=step_guess,
+                   surface_T=getattr(cfg, "surface_T", 0.0), circuit_R=getattr(cfg, "circuit_R", 0.0),
+                   circuit_C=getattr(cfg, "circuit_C", 0.0))
     return c, keep
 
 
