@@ -158,33 +158,63 @@ def measured_traffic(kernel: str):
     return None
 
 
-def cpu_baseline(cfg_name, sample, steps, np):
-    """The CPU oracle (single thread, FP64) on a bounded sample of the same
-    workload: `sample` particles with the same species mix and distributions
-    on the same grid, timed over `steps` steps of push, collisions and
-    deposit. The oracle's Poisson solve is left out (a solve of the
-    128 x 128 x 512 grid takes minutes on one core); a smooth synthetic
-    potential stands in for the field."""
+def _cpu_worker(arg):
+    """One single-threaded oracle process of the CPU baseline: set up its
+    sample, wait for the others, then time its steps."""
+    cfg_name, sub, steps, seed, barrier = arg
     import oracle
     from paper_2402_08404_amd import workloads as W
     cfg, counts, kT, region, _ = workload(cfg_name)
-    frac = sample / sum(counts)
-    sub = tuple(int(round(c * frac)) for c in counts)
     o = oracle.Oracle(cfg, laplace=False)
-    o.load(W.initial_load(cfg, counts=sub, kT_eV=kT, region=region, seed=cfg.seed + 7))
+    o.load(W.initial_load(cfg, counts=sub, kT_eV=kT, region=region, seed=seed))
     o.set_phi(W.synthetic_potential(cfg, o.V0))
     n = sum(s.n for s in o.sp)
+    barrier.wait()
     t0 = time.perf_counter()
     for _ in range(steps):
         o.push()
         o.collide()
         o.deposit()
         o.step_no += 1
-    dt = time.perf_counter() - t0
-    return {"value": n * steps / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} particles ({sub[0]} e, {sub[1]} Cu+, {sub[2]} Cu) of the same workload, {steps} steps "
-                      f"of push+collisions+deposit on the same grid, synthetic potential, solve excluded; "
-                      f"{dt:.1f} s"}
+    return n, time.perf_counter() - t0
+
+
+def cpu_baseline(cfg_name, sample, steps, np, procs=0):
+    """The CPU oracle (FP64, single-threaded C) on a bounded sample of the same
+    workload, run as `procs` concurrent processes (default: every host core
+    up to 16), each on its own sample of `sample` particles with the same
+    species mix and distributions on the same grid, timed over `steps` steps
+    of push, collisions and deposit; the rate is the total of the processes
+    over the slowest one's time. The oracle's Poisson solve is left out (a
+    solve of the 128 x 128 x 512 grid takes minutes on one core); a smooth
+    synthetic potential stands in for the field. Runs before the GPU is
+    touched (the processes are forked)."""
+    import multiprocessing as mp
+    cfg, counts, kT, region, _ = workload(cfg_name)
+    ncpu = os.cpu_count() or 1
+    procs = procs or min(16, ncpu)
+    frac = sample / sum(counts)
+    sub = tuple(int(round(c * frac)) for c in counts)
+    ctx = mp.get_context("fork")
+    barrier = ctx.Manager().Barrier(procs)
+    with ctx.Pool(procs) as pool:
+        res = pool.map(_cpu_worker, [(cfg_name, sub, steps, cfg.seed + 7 + k, barrier) for k in range(procs)])
+    n_tot = sum(n for n, _ in res)
+    t_max = max(t for _, t in res)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": n_tot * steps / t_max, "unit": "particle-steps/s", "cores": procs, "kind": "oracle",
+            "host": {"nproc": ncpu, "model": model},
+            "sample": f"{procs} processes of the single-threaded oracle, each {res[0][0]} particles ({sub[0]} e, "
+                      f"{sub[1]} Cu+, {sub[2]} Cu) of the same workload on the same grid, {steps} steps of "
+                      f"push+collisions+deposit, synthetic potential, solve excluded; slowest process "
+                      f"{t_max:.1f} s"}
 
 
 def main():
@@ -199,18 +229,26 @@ def main():
     ap.add_argument("--stencil-blocks", type=int, default=0, help="override the tuned block count of the solver kernels")
     ap.add_argument("--step-guess", type=int, default=1, choices=[0, 1],
                     help="step-solve guess: 0 previous potential, 1 linear extrapolation in time")
-    ap.add_argument("--cpu-sample", type=int, default=3_000_000)
+    ap.add_argument("--cpu-sample", type=int, default=1_500_000, help="particles per oracle process")
     ap.add_argument("--cpu-steps", type=int, default=5)
+    ap.add_argument("--cpu-procs", type=int, default=0, help="oracle processes of the CPU baseline (0: cores, <= 16)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--skip-zero-solve", action="store_true")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned warm-start leg (training on pairs of this run, then iteration counts)")
     ap.add_argument("--learned-pairs", type=int, default=16)
     ap.add_argument("--learned-iters", type=int, default=300)
-    ap.add_argument("--prof-steps", type=int, default=5,
-                    help="steps of the profiled pass after the timed region (per-kernel HIP-event timings)")
+    ap.add_argument("--prof-steps", type=int, default=0,
+                    help="steps of the profiled replay (per-phase and per-kernel HIP-event timings; 0: as many as "
+                         "the timed steps)")
     ap.add_argument("--unet", action="store_true",
                     help="time the warm-start network (forward, and forward + backward + Adam) at 1 x 512 x 128 x 128")
+    ap.add_argument("--learned-experiment", action="store_true",
+                    help="the learned warm-start experiment on the tiny workload's shape: pairs from plain runs at "
+                         "6 ... 14 GV/m, 7 and 13 GV/m held out, then iterations to 1e-8 from each guess")
+    ap.add_argument("--le-pairs", type=int, default=20000, help="training and held-out pairs of the experiment")
+    ap.add_argument("--le-iters", type=int, default=4000, help="Adam steps of the experiment")
+    ap.add_argument("--le-batch", type=int, default=16, help="mini-batch of the experiment")
     ap.add_argument("--batch", action="store_true",
                     help="the batched field sweep (16 instances at 6.0 ... 13.5 GV/m, 1 M - 40 M particles) instead")
     ap.add_argument("--batch-scale", type=float, default=1.0, help="scale factor of the sweep's particle counts")
@@ -240,6 +278,10 @@ def main():
     if args.trace_summary:
         print(json.dumps(trace_summary(args.trace_summary), indent=1))
         return
+    cpu_base = None
+    if not (args.no_cpu_baseline or args.calibrate_copy or args.batch or args.unet or args.learned_experiment):
+        print("[bench] cpu baseline (oracle processes)", file=sys.stderr, flush=True)
+        cpu_base = cpu_baseline(args.workload, args.cpu_sample, args.cpu_steps, __import__("numpy"), args.cpu_procs)
     import torch
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 4
@@ -256,6 +298,8 @@ def main():
     def log(*a):
         print(*a, file=sys.stderr, flush=True)
 
+    if args.learned_experiment:
+        return learned_experiment(args, log)
     if args.batch:
         return batch_main(args, log)
     if args.unet:
@@ -272,15 +316,20 @@ def main():
     tune = B.load_tuning(args.tuning).get(B.shape_key(cfg), {})
     stencil_blocks = int(args.stencil_blocks or tune.get("stencil_blocks", 0))
     args.sort_every = int(args.sort_every or tune.get("sort_every", 16))
-    sim = pic.Simulation(cfg, caps=caps, precision=pic.PIC_F32 if fp32 else pic.PIC_F64, solver=solver,
-                         step_rtol=1e-8, step_maxit=20000, sort_every=args.sort_every, stencil_blocks=stencil_blocks,
-                         step_guess=args.step_guess)
-    log(f"[bench] init done ({time.perf_counter() - t_setup:.1f} s), generating {sum(counts)} particles")
-    load = W.initial_load(cfg, counts=counts, kT_eV=kT, region=region,
-                          dtype=np.float32 if fp32 else np.float64)
-    sim.load(load)
-    del load
-    sim.step(1, pic.STEP_DEPOSIT)
+    def new_instance():
+        """An instance with the workload's load (the same seeded load every
+        time) and its deposit."""
+        s_ = pic.Simulation(cfg, caps=caps, precision=pic.PIC_F32 if fp32 else pic.PIC_F64, solver=solver,
+                            step_rtol=1e-8, step_maxit=20000, sort_every=args.sort_every,
+                            stencil_blocks=stencil_blocks, step_guess=args.step_guess)
+        ld = W.initial_load(cfg, counts=counts, kT_eV=kT, region=region, dtype=np.float32 if fp32 else np.float64)
+        s_.load(ld)
+        del ld
+        s_.step(1, pic.STEP_DEPOSIT)
+        return s_
+
+    sim = new_instance()
+    log(f"[bench] instance ready ({time.perf_counter() - t_setup:.1f} s), {sum(counts)} particles")
     nn = cfg.nx * cfg.ny * cfg.nz
     # CG iterations to 1e-8 from a zero guess (plain CG) and from V0 phi1
     cg_info = {}
@@ -297,7 +346,7 @@ def main():
     it0 = m0["cg_iters_total"]
 
     # timed region: the production path (no profiling events, solver
-    # iterations as captured graphs)
+    # iterations as captured graphs, collisions concurrent with the solve)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     sim.step(args.steps, pic.STEP_FULL)
@@ -305,32 +354,67 @@ def main():
     wall = time.perf_counter() - t0
     m1 = sim.moments()
     log(f"[bench] timed {args.steps} steps in {wall:.3f} s")
-    # profiled pass over the next steps: HIP events on the library stream
-    # around each phase and each hot kernel (the same kernels, launched one
-    # by one)
-    pic.pic_profile(sim.ctx, True)
-    pic.pic_timers(sim.ctx, reset=True)
-    it_p0 = m1["cg_iters_total"]
-    sim.step(args.prof_steps, pic.STEP_FULL)
-    tm = pic.pic_timers(sim.ctx, reset=True)
-    pic.pic_profile(sim.ctx, False)
-    m2 = sim.moments()
-    log(f"[bench] profiled {args.prof_steps} steps")
-
     n_avg = 0.5 * (m0["n_alive"].sum() + m1["n_alive"].sum())
-    n_prof = 0.5 * (m1["n_alive"].sum() + m2["n_alive"].sum())
-    ne_avg = 0.5 * (m1["n_alive"][0] + m2["n_alive"][0])
     ms_step = 1e3 * wall / args.steps
     value = n_avg * args.steps / wall
+    learned = learned_leg(sim, pic, args, log) if not args.no_learned else None
+    sim.close()
+
+    # profiled replay: a second instance from the same initial state runs the
+    # same warm-up and the same steps with HIP events on the library stream
+    # around each phase and each hot kernel (phases one after another, the
+    # same kernels launched one by one), so the per-phase times belong to the
+    # particle populations of the timed steps
+    simp = new_instance()
+    simp.solve(solver=solver, guess=pic.PIC_GUESS_PREVIOUS, rtol=1e-8, maxit=200000)
+    simp.step(args.warmup, pic.STEP_FULL)
+    psteps = args.prof_steps if args.prof_steps > 0 else args.steps
+    pic.pic_profile(simp.ctx, True)
+    pic.pic_timers(simp.ctx, reset=True)
+    mp = simp.moments()
+    it_p0 = mp["cg_iters_total"]
+    alive_steps = []
+    for _ in range(psteps):
+        a0 = int(mp["n_alive"].sum())
+        simp.step(1, pic.STEP_FULL)
+        mp = simp.moments()
+        alive_steps.append(0.5 * (a0 + int(mp["n_alive"].sum())))
+    tm = pic.pic_timers(simp.ctx, reset=True)
+    pic.pic_profile(simp.ctx, False)
+    iters_prof = int(mp["cg_iters_total"] - it_p0)
+    m2 = mp
+    simp.close()
+    log(f"[bench] profiled replay of {psteps} steps")
 
     def avg(name):
         ms, cnt = tm[name]
         return ms / cnt if cnt else float("nan")
 
-    psteps = args.prof_steps
+    # the particle path (push + deposit + binning + collisions + emission):
+    # algorithmic bytes per particle-step 60 B (read x, v, id; write x, v;
+    # write and read the cell key) and per node-step 32 B (read the field,
+    # clear and write the int64 charge)
     particle_ms = tm["inject"][0] + tm["particles"][0] + tm["collide"][0]
+    p_bytes = sum(60.0 * a + 32.0 * nn for a in alive_steps)
+    p_gbs = p_bytes / (particle_ms * 1e-3) / 1e9 if particle_ms else float("nan")
+    particle_path = {
+        "value": float(sum(alive_steps) / (particle_ms * 1e-3)) if particle_ms else None,
+        "unit": "particle-steps/s", "ms_per_step": particle_ms / psteps,
+        "alive_mean": float(np.mean(alive_steps)),
+        "roofline": {"bound": "hbm", "achieved": round(p_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(p_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_step": p_bytes / psteps},
+        "phases_ms_per_step": {k2: tm[k2][0] / psteps for k2 in
+                               ("inject", "particles", "push", "bin", "deposit", "collide", "mcc")},
+        "what": "emission + push/deposit/binning + collisions, HIP-event time on the library stream, profiled "
+                "replay of the timed steps (60 B per particle-step + 32 B per node-step algorithmic)"}
+    solve_ms = tm["solve"][0] / psteps
+    poisson = {"solves_per_s": 1e3 / solve_ms if solve_ms else None, "ms_per_solve": solve_ms,
+               "iters_per_solve": iters_prof / psteps, "solver": args.solver,
+               "what": "MG-preconditioned CG to a relative residual of 1e-8 plus the node field, HIP-event time"}
     k_push_e = avg("push_e")
-    pb = push_bytes(ne_avg, nn, fp32)
+    ne_avg = 0.5 * (m1["n_alive"][0] + m2["n_alive"][0])
+    pb = push_bytes(float(np.mean(alive_steps)) * 0.8, nn, fp32)
     kernels = {"push_electrons": {"avg_ms": k_push_e, "launches": tm["push_e"][1], "bytes": pb,
                                   "gbs": pb / (k_push_e * 1e-3) / 1e9}}
     # A solve launches its iterations in chunks, so some launches of the
@@ -338,7 +422,6 @@ def main():
     # total event time is divided by the iterations that did work (the
     # returning launches' few microseconds stay in the total, so the average
     # errs high and the bandwidth low).
-    iters_prof = int(m2["cg_iters_total"] - it_p0)
     for name, per_node in SOLVER_BYTES_PER_NODE.items():
         b = per_node * nn
         n_work = iters_prof if 0 < iters_prof <= tm[name][1] else tm[name][1]
@@ -374,25 +457,19 @@ def main():
                    "sort_every": args.sort_every,
                    "stencil_blocks": stencil_blocks or 1024},
         "roofline": roof,
+        "particle_path": particle_path,
+        "poisson": poisson,
         "profiled_pass_ms_per_step": {k2: tm[k2][0] / psteps for k2 in
                                       ("inject", "particles", "push", "collide", "mcc", "solve", "step")},
-        "particle_phases": {"value": float(n_prof * psteps / (particle_ms * 1e-3)) if particle_ms else None,
-                            "unit": "particle-steps/s", "what": "emission + push/deposit/binning + collisions, "
-                                                                "HIP-event time on the library stream (profiled pass)"},
         "kernels": kernels,
         "cg": dict(cg_info, step_iters_avg=(m1["cg_iters_total"] - it0) / args.steps,
-                   profiled_iters_avg=(m2["cg_iters_total"] - it_p0) / psteps),
+                   profiled_iters_avg=iters_prof / psteps),
         "alive": [int(x) for x in m1["n_alive"]],
         "events_total": [int(x) for x in m1["events"]],
     }
-    if not args.no_learned:
-        out["cg"]["learned"] = learned_leg(sim, pic, args, log)
-    if not args.no_cpu_baseline:
-        log("[bench] cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_sample, args.cpu_steps, np)
-    else:
-        out["cpu_baseline"] = None
-    sim.close()
+    if learned is not None:
+        out["cg"]["learned"] = learned
+    out["cpu_baseline"] = cpu_base
     print(json.dumps(out), flush=True)
 
 
@@ -507,6 +584,103 @@ def learned_leg(sim, pic, args, log):
             "solves": res,
             "plain_gain_vs_zero": res["plain_zero"]["iters"] / max(res["plain_learned"]["iters"], 1),
             "plain_gain_vs_laplace": res["plain_laplace"]["iters"] / max(res["plain_learned"]["iters"], 1)}
+
+
+def learned_experiment(args, log):
+    """The learned warm start at the tiny workload's shape (32 x 32 x 64
+    nodes): (x, y) pairs from plain FP64 runs of the tiny workload at apex
+    fields 6, 7, ..., 14 GV/m (one run per field, a pair every 5 steps after a
+    tight solve), the runs at 7 and 13 GV/m held out of training; the network
+    trained on the others by the library's kernels; then, on fresh runs at the
+    held-out fields, the iterations to a relative residual of 1e-8 of plain CG
+    and of MG-PCG from a zero guess, the previous step's potential, V0 phi1
+    and the learned guess (projected, judged by plain CG)."""
+    import dataclasses
+    import torch
+    from paper_2402_08404_amd import pic, warmstart
+    from paper_2402_08404_amd import workloads as W
+    base = W.tiny()
+    fields = [6e9, 7e9, 8e9, 9e9, 10e9, 11e9, 12e9, 13e9, 14e9]
+    held = {7e9, 13e9}
+    per_field = max(1, args.le_pairs // len(fields))
+    shape = (base.nz, base.ny, base.nx)
+    t0 = time.perf_counter()
+    xs, ys, xh, yh = [], [], [], []
+    for i, F in enumerate(fields):
+        X, Y = warmstart.collect_samples(base, fields=[F], per_field=per_field, steps_between=5,
+                                         counts=(20000, 200, 2000), seed=11 + 97 * i)
+        (xh if F in held else xs).append(X)
+        (yh if F in held else ys).append(Y)
+        log(f"[learned] field {F / 1e9:.0f} GV/m: {X.shape[0]} pairs ({time.perf_counter() - t0:.0f} s)")
+    Xt, Yt = torch.cat(xs), torch.cat(ys)
+    Xh, Yh = torch.cat(xh), torch.cat(yh)
+    t_data = time.perf_counter() - t0
+    net = pic.UNet(args.le_batch, *shape, seed=7)
+    t1 = time.perf_counter()
+    losses = warmstart.train(net, Xt, Yt, iters=args.le_iters, lr=1e-3, lr_final=3e-5, log_every=500)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    log(f"[learned] trained {args.le_iters} steps on {Xt.shape[0]} pairs in {t_train:.0f} s")
+    guess_net = pic.UNet(1, *shape, params=net.params)
+    guess_net.sync()
+    # held-out pairs: relative L2 error of the network's charge response
+    errs = []
+    for k in range(0, Xh.shape[0], max(1, Xh.shape[0] // 64)):
+        y = guess_net.forward(Xh[k:k + 1])
+        errs.append(float((y - Yh[k:k + 1]).norm() / Yh[k:k + 1].norm().clamp_min(1e-30)))
+    res = {}
+    for F in sorted(held):
+        cfg = dataclasses.replace(base, apex_field=F, seed=5000 + int(F / 1e9))
+        sim = pic.Simulation(cfg, caps=(200000, 20000, 8000), precision=pic.PIC_F64, solver=pic.PIC_SOLVER_MGCG,
+                             step_rtol=1e-10)
+        sim.load(W.initial_load(cfg, counts=(20000, 200, 2000), seed=6000 + int(F / 1e9)))
+        sim.step(1, pic.STEP_DEPOSIT)
+        sim.solve(solver=pic.PIC_SOLVER_MGCG, rtol=1e-10)
+        sim.step(60, pic.STEP_FULL)
+        rows = {}
+        for state in range(8):
+            sim.step(9, pic.STEP_FULL)
+            sim.step(1, pic.STEP_FULL & ~pic.STEP_SOLVE)   # phi is the previous step's potential
+            for sname, solver in (("plain", pic.PIC_SOLVER_CG), ("mgcg", pic.PIC_SOLVER_MGCG)):
+                for gname, guess in (("zero", pic.PIC_GUESS_ZERO), ("previous", pic.PIC_GUESS_PREVIOUS),
+                                     ("laplace", pic.PIC_GUESS_LAPLACE), ("learned", pic.PIC_GUESS_LEARNED)):
+                    pic.pic_set_learned_guess(sim.ctx, guess_net.net, 0, True)
+                    saved = sim.phi.clone()
+                    torch.cuda.synchronize()
+                    t2 = time.perf_counter()
+                    r = sim.solve(solver=solver, guess=guess, rtol=1e-8, maxit=200000)
+                    ms = 1e3 * (time.perf_counter() - t2)
+                    d = rows.setdefault(f"{sname}_{gname}", {"iters": [], "relres0": [], "ms": [], "fell_back": 0})
+                    d["iters"].append(r["iterations"])
+                    d["relres0"].append(r["relres0"])
+                    d["ms"].append(ms)
+                    d["fell_back"] += int(r["fell_back"])
+                    sim.phi.copy_(saved)
+            sim.solve(solver=pic.PIC_SOLVER_MGCG, guess=pic.PIC_GUESS_PREVIOUS, rtol=1e-10)
+        pic.pic_set_learned_guess(sim.ctx, None)
+        sim.close()
+        res[f"{F / 1e9:.0f}GVm"] = {k: {"iters_mean": float(np.mean(v["iters"])), "iters": v["iters"],
+                                        "relres0_mean": float(np.mean(v["relres0"])), "ms_mean": float(np.mean(v["ms"])),
+                                        "fell_back": v["fell_back"]} for k, v in rows.items()}
+        log(f"[learned] held-out {F / 1e9:.0f} GV/m: " +
+            ", ".join(f"{k} {np.mean(v['iters']):.1f}" for k, v in rows.items()))
+    gains = {f: {"plain_vs_zero": v["plain_zero"]["iters_mean"] / v["plain_learned"]["iters_mean"],
+                 "plain_vs_previous": v["plain_previous"]["iters_mean"] / v["plain_learned"]["iters_mean"],
+                 "mgcg_vs_zero": v["mgcg_zero"]["iters_mean"] / v["mgcg_learned"]["iters_mean"]}
+             for f, v in res.items()}
+    m = min(20, len(losses))
+    out = {"metric": "CG iterations to 1e-8: learned vs plain (held-out fields)", "value":
+           float(np.mean([g["plain_vs_zero"] for g in gains.values()])), "unit": "x fewer plain-CG iterations",
+           "higher_is_better": True, "data": "synthetic", "dtype": "bf16",
+           "config": {"workload": "tiny_32x32x64", "fields_GVm": [f / 1e9 for f in fields],
+                      "held_out_GVm": sorted(f / 1e9 for f in held), "train_pairs": int(Xt.shape[0]),
+                      "held_out_pairs": int(Xh.shape[0]), "adam_steps": args.le_iters, "batch": args.le_batch},
+           "data_s": t_data, "train_s": t_train, "loss_first": sum(losses[:m]) / m, "loss_last": sum(losses[-m:]) / m,
+           "held_out_relative_error": {"mean": float(np.mean(errs)), "max": float(np.max(errs)), "n": len(errs)},
+           "solves": res, "gains": gains}
+    net.close()
+    guess_net.close()
+    print(json.dumps(out), flush=True)
 
 
 def batch_main(args, log):

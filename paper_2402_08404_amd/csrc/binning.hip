@@ -3,7 +3,8 @@
 //
 // Elements are the slots of the three species concatenated (electrons, ions,
 // neutrals, each up to the slot count of the last push); the value of an
-// element is species << 30 | slot and its key the tile-major cell key
+// element is species << 30 | slot (stored with the particle's id, so that the
+// collision kernels read the ids in cell order) and its key the tile-major cell key
 // written by the push (removed particles carry no key and are left out).
 // The push counts the keys by integer atomics into off (count_key, one
 // atomic per run of equal keys in a wavefront: the arrays are kept nearly in
@@ -34,14 +35,15 @@ __device__ inline void elem_kv(const uint32_t* const key[3], const DevState* st,
 
 struct BinIn {
     const uint32_t* key[3];
+    const uint32_t* id[3];
     const uint32_t* rank[3];  // rank of each slot among the particles of its key (from the push)
     const DevState* st;
     uint32_t nkeys;
 };
 
-// bins[off[k] + rank] = value for every element with a key k
+// bins[off[k] + rank] = {value, id} for every element with a key k
 __global__ __launch_bounds__(kBlock) void k_bin_place(BinIn in, const uint32_t* __restrict__ off,
-                                                       uint32_t* __restrict__ bins) {
+                                                       uint2* __restrict__ bins) {
     const int64_t n = total_elems(in.st);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += stride) {
@@ -49,7 +51,8 @@ __global__ __launch_bounds__(kBlock) void k_bin_place(BinIn in, const uint32_t* 
         elem_kv(in.key, in.st, e, k, v);
         if (k >= in.nkeys) continue;
         const int s = (int)(v >> 30);
-        bins[off[k] + in.rank[s][v & 0x3FFFFFFFu]] = v;
+        const uint32_t i = v & 0x3FFFFFFFu;
+        bins[off[k] + in.rank[s][i]] = make_uint2(v, in.id[s][i]);
     }
 }
 
@@ -61,6 +64,7 @@ hipError_t cell_bins(pic_ctx* c) {
     BinIn in;
     for (int s = 0; s < 3; ++s) {
         in.key[s] = c->key[s];
+        in.id[s] = c->buf.id[s];
         in.rank[s] = c->rank + (s >= 1 ? c->buf.cap[0] : 0) + (s == 2 ? c->buf.cap[1] : 0);
     }
     in.st = c->st;

@@ -308,7 +308,7 @@ template <typename T>
 struct DepositArgs {
     Species<T> e, ion;
     const uint32_t* off;
-    const uint32_t* bins;
+    const uint2* bins;
     int64_t* rho;
     Grid g;
     DevState* st;
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_deposit_tiles(DepositArgs<T> a) {
     for (int m = threadIdx.x; m < N1 * N1 * N1; m += blockDim.x) q[m] = 0ull;
     __syncthreads();
     for (uint32_t b = b0 + threadIdx.x; b < b1; b += blockDim.x) {
-        uint32_t e = a.bins[b];
+        uint32_t e = a.bins[b].x;
         uint32_t s = e >> 30;
         if (s == PIC_NEUTRAL) continue;
         uint32_t i = e & 0x3FFFFFFFu;
@@ -389,7 +389,7 @@ struct MccArgs {
     Species<T> sp[3];
     Grid g;
     const uint32_t* off;
-    uint32_t* bins;
+    uint2* bins;
     int64_t nc;  // number of cell keys
     uint32_t* big;
     uint32_t* mcc_list;   // small cells for the full collision pass, one segment per scanning wavefront
@@ -637,10 +637,10 @@ __device__ inline void mcc_cell(const MccArgs<T>& a, uint32_t c, uint32_t o0, in
     uint64_t kk[kSmallCell];
     uint32_t ee[kSmallCell];
     for (int t = 0; t < n; ++t) {
-        uint32_t e = a.bins[o0 + t];
+        const uint2 be = a.bins[o0 + t];
+        uint32_t e = be.x;
         uint32_t s = e >> 30;
-        uint32_t id = a.sp[s].id[e & 0x3FFFFFFFu];
-        uint64_t k = ((uint64_t)s << 32) | id;
+        uint64_t k = ((uint64_t)s << 32) | be.y;
         int u = t;
         while (u > 0 && kk[u - 1] > k) {
             kk[u] = kk[u - 1];
@@ -651,7 +651,7 @@ __device__ inline void mcc_cell(const MccArgs<T>& a, uint32_t c, uint32_t o0, in
         ee[u] = e;
     }
     if (a.write_sorted)
-        for (int t = 0; t < n; ++t) a.bins[o0 + t] = ee[t];
+        for (int t = 0; t < n; ++t) a.bins[o0 + t] = make_uint2(ee[t], (uint32_t)kk[t]);
     int ne = 0, ni = 0;
     for (int t = 0; t < n; ++t) {
         uint32_t s = (uint32_t)(kk[t] >> 32);
@@ -675,13 +675,15 @@ template <typename T>
 __device__ inline bool mcc_probe(const MccArgs<T>& a, uint32_t o0, int n, const double (*pn)[kSmallCell + 1]) {
     uint32_t e[kSmallCell], id[kSmallCell];
 #pragma unroll
-    for (int t = 0; t < kSmallCell; ++t) e[t] = a.bins[o0 + (t < n ? t : 0)];
+    for (int t = 0; t < kSmallCell; ++t) {
+        const uint2 be = a.bins[o0 + (t < n ? t : 0)];
+        e[t] = be.x;
+        id[t] = be.y;
+    }
     int cs[3] = {0, 0, 0};
 #pragma unroll
     for (int t = 0; t < kSmallCell; ++t) {
-        const uint32_t sp = e[t] >> 30, slot = e[t] & 0x3FFFFFFFu;
-        const uint32_t* ids = sp == 0 ? a.sp[0].id : (sp == 1 ? a.sp[1].id : a.sp[2].id);
-        id[t] = ids[slot];
+        const uint32_t sp = e[t] >> 30;
         if (t < n) cs[sp] += 1;
     }
     // projectiles of each class as bit masks over the cell's entries
@@ -851,9 +853,10 @@ __global__ __launch_bounds__(64) void k_mcc_big(MccArgs<T> a) {
         while (P < n) P <<= 1;
         for (int t = lane; t < P; t += 64) {
             if (t < n) {
-                uint32_t e = a.bins[o0 + t];
+                const uint2 be = a.bins[o0 + t];
+                uint32_t e = be.x;
                 uint32_t s = e >> 30;
-                kk[t] = ((uint64_t)s << 32) | a.sp[s].id[e & 0x3FFFFFFFu];
+                kk[t] = ((uint64_t)s << 32) | be.y;
                 ee[t] = e;
             } else {
                 kk[t] = ~0ull;
@@ -882,7 +885,7 @@ __global__ __launch_bounds__(64) void k_mcc_big(MccArgs<T> a) {
             }
         }
         if (a.write_sorted)
-            for (int t = lane; t < n; t += 64) a.bins[o0 + t] = ee[t];
+            for (int t = lane; t < n; t += 64) a.bins[o0 + t] = make_uint2(ee[t], (uint32_t)kk[t]);
         int ne = 0, ni = 0;
         for (int t = lane; t < n; t += 64) {
             uint32_t s = (uint32_t)(kk[t] >> 32);
@@ -1063,12 +1066,12 @@ __global__ void k_words(const DevState* st, uint32_t* words, int64_t maxw) {
 // (canonically sorted) cell bins; particles appended after the bins were
 // built (products) follow in their order.
 
-__global__ void k_sort_flags(int sp, const uint32_t* bins, const uint32_t* nbins, const uint32_t* const* ids,
+__global__ void k_sort_flags(int sp, const uint2* bins, const uint32_t* nbins, const uint32_t* const* ids,
                              uint32_t* flag, int64_t cap) {
     int64_t n = (int64_t)*nbins;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n && j < cap; j += stride) {
-        uint32_t e = bins[j];
+        uint32_t e = bins[j].x;
         uint32_t s = e >> 30;
         flag[j] = (s == (uint32_t)sp) && ids[s][e & 0x3FFFFFFFu] != kDead;
     }
@@ -1078,7 +1081,7 @@ template <typename T>
 struct SortArgs {
     Species<T> s;
     int sp;
-    const uint32_t* bins;
+    const uint2* bins;
     const uint32_t* nbins;
     const uint32_t* flag;   // flags (before the scan)
     const uint32_t* rank;   // exclusive ranks
@@ -1094,7 +1097,7 @@ __global__ void k_sort_gather(SortArgs<T> a) {
     int64_t cap = a.s.cap;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += stride) {
-        uint32_t e = a.bins[j];
+        uint32_t e = a.bins[j].x;
         if ((e >> 30) != (uint32_t)a.sp) continue;
         uint32_t i = e & 0x3FFFFFFFu;
         if (a.s.id[i] == kDead) continue;

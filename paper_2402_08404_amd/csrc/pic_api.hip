@@ -148,7 +148,7 @@ size_t pic::scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[
     t->xs = (double*)take(5 * (size_t)cfg->xs_n * sizeof(double));  // el, iz, cx, rate bounds of the two classes
     t->off = (uint32_t*)take((nc + 1) * 4);
     for (int s = 0; s < 3; ++s) t->key[s] = (uint32_t*)take(cap[s] * 4);
-    t->bins = (uint32_t*)take(capsum * 4);
+    t->bins = (uint2*)take(capsum * 8);
     t->big = (uint32_t*)take(nc * 4);
     t->mcc_list = (uint32_t*)take(nc * 4);
     t->mcc_count = (uint32_t*)take(4 * 8192 * 4);

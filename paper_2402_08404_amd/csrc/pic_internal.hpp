@@ -378,7 +378,7 @@ struct pic_ctx {
     double* xs = nullptr;         // 3 * xs_n
     uint32_t* off = nullptr;      // nkeys + 1
     uint32_t* key[3] = {};
-    uint32_t* bins = nullptr;     // sum cap
+    uint2* bins = nullptr;        // sum cap: {species << 30 | slot, id} in cell order
     uint32_t* big = nullptr;      // big-cell list (nkeys)
     uint32_t* mcc_list = nullptr;   // small cells for the full collision pass (nkeys)
     uint32_t* mcc_count = nullptr;  // cells per scanning wavefront (4 x 8192)

@@ -18,7 +18,7 @@ from . import workloads as W
 
 
 def collect_samples(base: W.Config, fields, per_field: int, steps_between: int, counts, region="near_tip",
-                    kT_eV=None, caps=None, seed=11, solve_rtol=1e-12, device="cuda"):
+                    kT_eV=None, caps=None, seed=11, solve_rtol=1e-12, device="cuda", log_every: int = 500):
     """(x, y) pairs as fp32 device tensors of shape [nz][ny][nx]: for each apex
     field, a fresh instance with its own load, sampled every steps_between
     full steps after a solve to solve_rtol."""
@@ -44,6 +44,8 @@ def collect_samples(base: W.Config, fields, per_field: int, steps_between: int, 
                 torch.cuda.synchronize(device)
                 xs.append(x)
                 ys.append(y)
+                if log_every and k % log_every == log_every - 1:
+                    print(f"[warmstart] field {F / 1e9:.1f} GV/m: {k + 1} pairs", flush=True)
         finally:
             sim.close()
     return torch.stack(xs), torch.stack(ys)

@@ -54,3 +54,40 @@ def test_autotune_picks_candidates():
     assert set(t) == {batch.shape_key(c) for c, _ in its}
     for v in t.values():
         assert v["sort_every"] in (8, 16) and v["stencil_blocks"] in (256, 1024)
+
+
+def test_batched_instance_matches_oracle():
+    """Each instance of a concurrently stepped FP64 batch against the FP64
+    oracle run on the same configuration and load: three whole steps with
+    identical events and node charge, particles to rounding (decisions that
+    the oracle reports as fragile end the comparison of that instance)."""
+    import oracle
+    from paper_2402_08404_amd import batch, pic
+    from paper_2402_08404_amd import workloads as W
+    from gpu_common import compare_states, event_sets
+    its = items()
+    b = batch.Batch(its, kT_eV=(2.0, 0.5, 0.05), region="box", precision=pic.PIC_F64, step_rtol=1e-12)
+    orcs = []
+    for k, (cfg, counts) in enumerate(its):
+        o = oracle.Oracle(cfg)
+        o.load(W.initial_load(cfg, counts=counts, kT_eV=(2.0, 0.5, 0.05), region="box", seed=7 + k))
+        o.deposit()
+        o.solve(rtol=1e-12)
+        orcs.append(o)
+    live = set(range(len(its)))
+    compared = 0
+    for step in range(3):
+        b.step(1, pic.STEP_FULL | pic.STEP_EVENTS)
+        for k in sorted(live):
+            o, sim = orcs[k], b.sims[k]
+            o.step(rtol=1e-12)
+            if o.last_fragile:
+                live.discard(k)
+                continue
+            assert event_sets(sim.events(), set()) == event_sets(o.last_events, set()), (k, step)
+            compare_states(its[k][0], sim.state(), o.state(), 1e-11, 1e-9)
+            assert np.array_equal(sim.grid("rho"), o.Q), (k, step)
+            compared += 1
+    b.close()
+    print("instance-steps compared", compared, flush=True)
+    assert compared >= 9
