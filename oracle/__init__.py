@@ -49,13 +49,14 @@ class _Config(C.Structure):
                 ("xs_emin", C.c_double), ("xs_emax", C.c_double),
                 ("xs_el", C.POINTER(C.c_double)), ("xs_iz", C.POINTER(C.c_double)),
                 ("xs_cx", C.POINTER(C.c_double)), ("seed", C.c_uint64),
-                ("fn_rings", C.c_int32), ("fn_az", C.c_int32)]
+                ("fn_rings", C.c_int32), ("fn_az", C.c_int32), ("w_max", C.c_int32), ("pad", C.c_int32),
+                ("n_max", C.c_double)]
 
 
 class _Species(C.Structure):
     _fields_ = [("n", C.c_int64), ("cap", C.c_int64)] + \
                [(k, C.POINTER(C.c_double)) for k in ("x", "y", "z", "vx", "vy", "vz")] + \
-               [("id", C.POINTER(C.c_uint32))]
+               [("id", C.POINTER(C.c_uint32)), ("w", C.POINTER(C.c_uint32))]
 
 
 class _Event(C.Structure):
@@ -66,7 +67,8 @@ class _Event(C.Structure):
 class _CollideOut(C.Structure):
     _fields_ = [("ev", C.POINTER(_Event)), ("ev_cap", C.c_int64), ("n_ev", C.c_int64),
                 ("fragile", C.POINTER(C.c_uint32)), ("fr_cap", C.c_int64), ("n_fragile", C.c_int64),
-                ("n_kind", C.c_int64 * 5), ("n_bsi_skip", C.c_int64)]
+                ("n_kind", C.c_int64 * 5), ("n_bsi_skip", C.c_int64), ("n_kind_w", C.c_int64 * 5),
+                ("n_split", C.c_int64)]
 
 
 _lib = None
@@ -154,7 +156,7 @@ def _load(path: str):
     L.orc_evap_flux.argtypes = [cfgp, C.c_double]
     L.orc_evap_flux.restype = C.c_double
     L.orc_evaporate.argtypes = [cfgp, C.c_uint32, C.c_double, C.POINTER(_Species), C.POINTER(C.c_uint32),
-                                C.POINTER(C.c_double)]
+                                C.POINTER(C.c_double), i64p]
     L.orc_evaporate.restype = C.c_int64
     return L
 
@@ -168,7 +170,8 @@ def make_config(cfg) -> tuple[_Config, list]:
                 tip_h=cfg.tip_h, dt=cfg.dt, phi_w=cfg.phi_w, xi=cfg.xi, m_ion=cfg.m_ion,
                 xs_emin=cfg.xs_emin, xs_emax=cfg.xs_emax,
                 xs_el=keep[0].ctypes.data_as(dpp), xs_iz=keep[1].ctypes.data_as(dpp),
-                xs_cx=keep[2].ctypes.data_as(dpp), seed=cfg.seed, fn_rings=cfg.fn_rings, fn_az=cfg.fn_az)
+                xs_cx=keep[2].ctypes.data_as(dpp), seed=cfg.seed, fn_rings=cfg.fn_rings, fn_az=cfg.fn_az,
+                w_max=int(getattr(cfg, "w_max", 1)), n_max=float(getattr(cfg, "n_max", 1e24)))
     return c, keep
 
 
@@ -189,17 +192,20 @@ def uniform(hi: int, lo: int) -> float:
 
 
 class _SpeciesStore:
-    """Growable SoA arrays of one species (FP64 grid units, uint32 ids)."""
+    """Growable SoA arrays of one species (FP64 grid units, uint32 ids and
+    superparticle weights)."""
 
     def __init__(self, cap: int):
         self.cap = int(cap)
         self.n = 0
         self.a = {k: np.zeros(self.cap) for k in ("x", "y", "z", "vx", "vy", "vz")}
         self.id = np.zeros(self.cap, np.uint32)
+        self.w = np.ones(self.cap, np.uint32)
 
     def view(self) -> _Species:
         dpp = C.POINTER(C.c_double)
-        s = _Species(n=self.n, cap=self.cap, id=self.id.ctypes.data_as(C.POINTER(C.c_uint32)),
+        u32 = C.POINTER(C.c_uint32)
+        s = _Species(n=self.n, cap=self.cap, id=self.id.ctypes.data_as(u32), w=self.w.ctypes.data_as(u32),
                      **{k: v.ctypes.data_as(dpp) for k, v in self.a.items()})
         return s
 
@@ -214,6 +220,9 @@ class _SpeciesStore:
         b = np.zeros(new, np.uint32)
         b[: self.n] = self.id[: self.n]
         self.id = b
+        b = np.ones(new, np.uint32)
+        b[: self.n] = self.w[: self.n]
+        self.w = b
         self.cap = new
 
     def keep(self, mask: np.ndarray):
@@ -221,11 +230,13 @@ class _SpeciesStore:
         for k in self.a:
             self.a[k][:m] = self.a[k][: self.n][mask]
         self.id[:m] = self.id[: self.n][mask]
+        self.w[:m] = self.w[: self.n][mask]
         self.n = m
 
     def arrays(self) -> dict:
         d = {k: v[: self.n].copy() for k, v in self.a.items()}
         d["id"] = self.id[: self.n].copy()
+        d["w"] = self.w[: self.n].copy()
         return d
 
 
@@ -276,8 +287,14 @@ class Oracle:
         self.i_gap = 0.0              # Shockley-Ramo current of the last push [A]
         self.i_tot = 0.0              # circuit current of the last circuit step [A]
         self.bomb_energy = np.zeros(2)  # kinetic energy of ions absorbed at the cathode plane and the tip [J]
-        self.evaporated = 0
+        self.evaporated = 0           # evaporated superparticles
+        self.evap_atoms = 0           # evaporated atoms (the sum of their weights)
         self.evap_expected = 0.0
+        # superparticles per cell at the last binning (after the last push),
+        # read by the weight rule of the evaporated neutrals
+        self.cell_count = np.zeros((cfg.nx - 1) * (cfg.ny - 1) * (cfg.nz - 1), np.int64)
+        self.events_w = np.zeros(5, np.int64)     # physical collisions per kind (sum of N_coll)
+        self.splits = 0
         self.last_events = []
         self.last_fragile = set()
         self.last_solve = (0, 0.0)
@@ -296,6 +313,7 @@ class Oracle:
             for k in ("x", "y", "z", "vx", "vy", "vz"):
                 st.a[k][st.n: st.n + n] = np.asarray(a[k], np.float64)
             st.id[st.n: st.n + n] = np.arange(self.next_id, self.next_id + n, dtype=np.uint32)
+            st.w[st.n: st.n + n] = np.asarray(a["w"], np.uint32) if "w" in a else 1
             st.n += n
             self.next_id += n
 
@@ -368,14 +386,31 @@ class Oracle:
         nid = C.c_uint32(self.next_id)
         nexp = C.c_double(0.0)
         k = self.L.orc_evaporate(C.byref(self.c), self.step_no, self.cfg.surface_T, C.byref(v), C.byref(nid),
-                                 C.byref(nexp))
+                                 C.byref(nexp), self.cell_count)
         if k < 0:
             raise RuntimeError("oracle: evaporation capacity")
+        n0 = st.n
         st.n = int(v.n)
         self.next_id = nid.value
         self.evaporated += k
+        self.evap_atoms += int(st.w[n0: st.n].sum())
         self.evap_expected += nexp.value
         return k
+
+    def bin_counts(self):
+        """Superparticles per cell of the current positions (all species), as
+        the binning of a push or deposit phase counts them."""
+        cc = np.zeros_like(self.cell_count)
+        nx1, ny1 = self.cfg.nx - 1, self.cfg.ny - 1
+        for st in self.sp:
+            if st.n == 0:
+                continue
+            i = np.clip(np.floor(st.a["x"][: st.n]).astype(np.int64), 0, nx1 - 1)
+            j = np.clip(np.floor(st.a["y"][: st.n]).astype(np.int64), 0, ny1 - 1)
+            k = np.clip(np.floor(st.a["z"][: st.n]).astype(np.int64), 0, self.cfg.nz - 2)
+            np.add.at(cc, (k * ny1 + j) * nx1 + i, 1)
+        self.cell_count = cc
+        return cc
 
     def push(self) -> list:
         """Leapfrog push and removal (Sec. 2.2). Also: with the circuit on, the
@@ -401,9 +436,11 @@ class Oracle:
                 for j, k in ((0, CATHODE), (1, TIP)):
                     m = code == k
                     v2 = (st.a["vx"][: st.n][m] ** 2 + st.a["vy"][: st.n][m] ** 2 + st.a["vz"][: st.n][m] ** 2)
-                    self.bomb_energy[j] += float(np.sum(0.5 * self.masses[s] * v2 * sv * sv))
+                    w = st.w[: st.n][m].astype(np.float64)
+                    self.bomb_energy[j] += float(np.sum(w * 0.5 * self.masses[s] * v2 * sv * sv))
             st.keep(code == ALIVE)
             codes.append(code)
+        self.bin_counts()
         return codes
 
     def circuit_step(self, i_gap: float):
@@ -416,8 +453,11 @@ class Oracle:
 
     def collide(self, flags: int = COLL_ALL):
         n_neu = self.sp[SP_NEU].n
+        # room for the products (one ion and one electron per neutral) and for
+        # a split-off superparticle of every particle
         for s in (SP_E, SP_ION):
-            self.sp[s].ensure(n_neu + 1)
+            self.sp[s].ensure(n_neu + self.sp[s].n + 1)
+        self.sp[SP_NEU].ensure(n_neu + 1)
         cap = 2 * (n_neu + self.sp[SP_E].n + self.sp[SP_ION].n) + 16
         ev = (_Event * cap)()
         fr = np.zeros(cap, np.uint32)
@@ -434,6 +474,8 @@ class Oracle:
         self.last_fragile = set(int(x) for x in fr[: int(out.n_fragile)])
         for k in range(5):
             self.events[k] += out.n_kind[k]
+            self.events_w[k] += out.n_kind_w[k]
+        self.splits += int(out.n_split)
         self.bsi_skips += int(out.n_bsi_skip)
         return self.last_events
 
@@ -460,7 +502,9 @@ class Oracle:
                 "q_total": int(self.Q.sum()), "absorbed": self.absorbed.copy(),
                 "events": self.events.copy(), "injected": self.injected, "v_gap": self.V_gap,
                 "i_gap": self.i_gap, "i_tot": self.i_tot, "bomb_energy": self.bomb_energy.copy(),
-                "evaporated": self.evaporated, "evap_expected": self.evap_expected}
+                "evaporated": self.evaporated, "evap_atoms": self.evap_atoms, "evap_expected": self.evap_expected,
+                "n_phys": np.array([int(st.w[: st.n].sum()) for st in self.sp], np.int64),
+                "events_w": self.events_w.copy(), "splits": self.splits}
 
     # -- helpers for tests ----------------------------------------------------
     def gather(self, E: np.ndarray, X, Y, Z) -> np.ndarray:

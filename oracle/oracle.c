@@ -33,6 +33,9 @@
 #define TAG_FI 5u
 #define TAG_INJ 6u
 
+/* Weight of superparticle p (Sec. 2.3.2), 1 without a weight array. */
+static uint32_t wgt(const orc_species* s, int64_t p) { return s->w ? s->w[p] : 1u; }
+
 /* Relative band inside which two correct libm implementations may disagree on
  * a decision U < P; decisions that close are reported as fragile. */
 #define FRAGILE_REL 1.4210854715202004e-14 /* 2^-46 */
@@ -338,7 +341,7 @@ void orc_push_sr(const orc_config* c, const double* E, const double* E0, orc_spe
             if (E0) {
                 double w[3];
                 orc_gather(c, E0, s->x[p], s->y[p], s->z[p], w);
-                sr += q * (vx * w[0] + vy * w[1] + vz * w[2]);
+                sr += (double)wgt(s, p) * q * (vx * w[0] + vy * w[1] + vz * w[2]);
             }
         }
         s->x[p] += s->vx[p];
@@ -379,8 +382,9 @@ void orc_deposit(const orc_config* c, const orc_species* s, int64_t sign, int64_
         int64_t qx = quantize(X - i, 13), qy = quantize(Y - j, 13), qz = quantize(Z - k, 14);
         int64_t wx[2] = {8192 - qx, qx}, wy[2] = {8192 - qy, qy}, wz[2] = {16384 - qz, qz};
         int64_t base = ((int64_t)k * c->ny + j) * c->nx + i;
+        int64_t sw = sign * (int64_t)wgt(s, p);     /* a superparticle of weight w carries w charges */
         for (int t = 0; t < 8; ++t)
-            Q[corner(c, base, t)] += sign * wx[t & 1] * wy[(t >> 1) & 1] * wz[(t >> 2) & 1];
+            Q[corner(c, base, t)] += sw * wx[t & 1] * wy[(t >> 1) & 1] * wz[(t >> 2) & 1];
     }
 }
 
@@ -504,6 +508,7 @@ int64_t orc_fn_inject(const orc_config* c, uint32_t step, const double* phi, orc
             e->z[m] = g[2] + 1e-3 * g[5];
             e->vx[m] = e->vy[m] = e->vz[m] = 0.0;
             e->id[m] = (*next_id)++;
+            if (e->w) e->w[m] = 1u;
             ++added;
         }
     }
@@ -537,8 +542,22 @@ double orc_evap_flux(const orc_config* c, double T) {
     return P_ATM / sqrt(2.0 * PI * c->m_ion * K_B * T) * exp(E_VAP_CU * E_CH / K_B * (1.0 / T_BOIL_CU - 1.0 / T));
 }
 
+/* Weight of the superparticles injected at one surface location (Sec. 2.3.2):
+ * w = min(ceil(max(1, sqrt((n_cell / n_max)(N_inj / w_min)))) w_min, w_max)
+ * with w_min = 1, N_inj the atoms injected there in the step and n_cell the
+ * superparticle number density of the cell above the location (reading: the
+ * cell of the field point one spacing out along the normal, counted at the
+ * last binning of the particles, i.e. after the last push). */
+static int64_t inject_weight(const orc_config* c, int64_t n_inj, int64_t cell_sp) {
+    if (c->w_max <= 1 || n_inj <= 1) return 1;
+    double n_cell = (double)cell_sp / (c->h * c->h * c->h);
+    double r = sqrt(n_cell / c->n_max * (double)n_inj);
+    double w = ceil(r > 1.0 ? r : 1.0);
+    return w < (double)c->w_max ? (int64_t)w : (int64_t)c->w_max;
+}
+
 int64_t orc_evaporate(const orc_config* c, uint32_t step, double T, orc_species* nsp, uint32_t* next_id,
-                      double* n_expected) {
+                      double* n_expected, const int64_t* cell_count) {
     int64_t np = orc_fn_patch_count(c), added = 0;
     double h = c->h, flux = orc_evap_flux(c, T);
     double sig = sqrt(K_B * T / c->m_ion) * c->dt / h;   /* grid units per step */
@@ -550,7 +569,11 @@ int64_t orc_evaporate(const orc_config* c, uint32_t step, double T, orc_species*
         double u0, u1;
         draw2(c, (uint32_t)p, step, TAG_EVAP, 0, &u0, &u1);
         double fl = floor(N);
-        int64_t k = (int64_t)fl + ((u0 < N - fl) ? 1 : 0);
+        int64_t atoms = (int64_t)fl + ((u0 < N - fl) ? 1 : 0);
+        /* atoms -> superparticles of weight wp (the last one takes the rest) */
+        int64_t cnt = cell_count ? cell_count[orc_cell_of(c, g[0] + g[3], g[1] + g[4], g[2] + g[5])] : 0;
+        int64_t wp = inject_weight(c, atoms, cnt);
+        int64_t k = (atoms + wp - 1) / wp;
         if (!grow_ok(nsp, k)) return -1;
         for (int64_t j = 0; j < k; ++j) {
             double ua, ub, w1, w2, w3, unused;
@@ -573,6 +596,7 @@ int64_t orc_evaporate(const orc_config* c, uint32_t step, double T, orc_species*
             nsp->vy[m] = vn * n[1] + va * t1[1] + vb * t2[1];
             nsp->vz[m] = vn * n[2] + va * t1[2] + vb * t2[2];
             nsp->id[m] = (*next_id)++;
+            if (nsp->w) nsp->w[m] = (uint32_t)(j + 1 < k ? wp : atoms - (k - 1) * wp);
             ++added;
         }
     }
@@ -593,7 +617,32 @@ static int entry_cmp(const void* a, const void* b) {
     return 0;
 }
 
-typedef struct product { int32_t kind; uint32_t nid; int64_t nidx; int64_t ev; double ve[3]; } product;
+typedef struct product { int32_t kind; uint32_t nid; int64_t nidx; int64_t ev; double ve[3]; uint32_t c; } product;
+
+/* A superparticle split off by a partial collision (Sec. 2.3.2): c of the
+ * parent's weight units leave with the velocity v; the parent keeps the rest
+ * and its velocity. Ordered by (species, parent id). */
+typedef struct split { int32_t sp; uint32_t pid; int64_t pidx; double v[3]; uint32_t c; } split;
+
+static int split_cmp(const void* a, const void* b) {
+    const split* x = a; const split* y = b;
+    if (x->sp != y->sp) return x->sp < y->sp ? -1 : 1;
+    if (x->pid != y->pid) return x->pid < y->pid ? -1 : 1;
+    return 0;
+}
+
+/* The c collided units of superparticle p of species s take velocity v: in
+ * place when they are the whole superparticle, else split off. */
+static void collided_units(orc_species* S, int s, int64_t p, const double v[3], uint32_t c, split* spl,
+                           int64_t* nspl) {
+    if (c >= wgt(S, p)) {
+        S->vx[p] = v[0]; S->vy[p] = v[1]; S->vz[p] = v[2];
+        return;
+    }
+    split* q = &spl[(*nspl)++];
+    q->sp = s; q->pid = S->id[p]; q->pidx = p; q->c = c;
+    q->v[0] = v[0]; q->v[1] = v[1]; q->v[2] = v[2];
+}
 
 static int product_cmp(const void* a, const void* b) {
     const product* x = a; const product* y = b;
@@ -654,10 +703,21 @@ static void elastic_du(const double u[3], double ct2, double ph2, double du[3]) 
  *  - the energy for sigma is (1/2) m_e u^2 for (e,Cu) and (1/2) m_Cu u^2 for
  *    (Cu+,Cu); ionization needs more than xi;
  *  - a particle takes part in at most one event per step: a neutral that had
- *    an (e,Cu) event is kept in the (Cu+,Cu) pairing but its pair is void. */
+ *    an (e,Cu) event is kept in the (Cu+,Cu) pairing but its pair is void.
+ * Superparticle weights (Sec. 2.3.2, weights in units of w_min = 1): the
+ * lighter superparticle of a pair is cut into N_p = min(w_a, w_b)
+ * sub-particles of weight 1, each colliding with the heavier one (weight w_t)
+ * with P = 1 - exp(-u n w_p w_t sigma dt), w_p = 1; N_coll counts the
+ * sub-particles with U_i < P (U_0 is the pair's first draw, U_i for i >= 1
+ * from the counter (projectile id, step, tag + 16, i)). The pair's event, its
+ * process and its angles are drawn once; the N_coll collided units of each
+ * side take the outcome, split off as a new superparticle where they are not
+ * the whole of it (the rest keeps its velocity). With every weight 1 this is
+ * the unweighted collision above. */
+#define TAG_SUB 16u
 static void mcc_class(const orc_config* c, uint32_t step, int cls, const entry* ent, int64_t ne,
                       orc_species* sp, uint8_t* used[3], product* prod, int64_t* nprod,
-                      orc_collide_out* o) {
+                      split* spl, int64_t* nspl, orc_collide_out* o) {
     int sa = (cls == 1) ? ORC_SP_E : ORC_SP_ION;
     int sb = ORC_SP_NEU;
     double ma = (cls == 1) ? M_EL : c->m_ion, mb = c->m_ion;
@@ -710,11 +770,20 @@ static void mcc_class(const orc_config* c, uint32_t step, int cls, const entry* 
                 }
                 double stot = 0.0;
                 for (int k = 0; k < nproc; ++k) stot += sig[k];
-                double P = -expm1(-um * n * stot * dt);
+                uint32_t wa = wgt(A, ia), wb = wgt(B, ib);
+                uint32_t wt = wa > wb ? wa : wb, npart = wa < wb ? wa : wb;
+                double P = -expm1(-um * n * (double)wt * stot * dt);
                 double U1, U2;
                 draw2(c, pe->id, step, cls == 1 ? TAG_MCC1 : TAG_MCC2, 0, &U1, &U2);
                 if (P > 0.0 && fabs(U1 - P) <= FRAGILE_REL * P) fragile_add(o, pe->id);
-                if (!(U1 < P)) continue;
+                uint32_t ncoll = (U1 < P) ? 1u : 0u;
+                for (uint32_t q = 1; q < npart; ++q) {
+                    double Uq, unq;
+                    draw2(c, pe->id, step, (cls == 1 ? TAG_MCC1 : TAG_MCC2) + TAG_SUB, q, &Uq, &unq);
+                    if (P > 0.0 && fabs(Uq - P) <= FRAGILE_REL * P) fragile_add(o, pe->id);
+                    if (Uq < P) ++ncoll;
+                }
+                if (ncoll == 0) continue;
                 int proc = nproc - 1;
                 double cum = 0.0;
                 for (int k = 0; k < nproc; ++k) {
@@ -729,9 +798,12 @@ static void mcc_class(const orc_config* c, uint32_t step, int cls, const entry* 
                     draw2(c, pe->id, step, TAG_MCC1, 1, &u3, &u4);
                     elastic_du(u, 2.0 * u3 - 1.0, 2.0 * PI * u4, du);
                     double ka = mu / ma * dt / h, kb = mu / mb * dt / h;
-                    A->vx[ia] += ka * du[0]; A->vy[ia] += ka * du[1]; A->vz[ia] += ka * du[2];
-                    B->vx[ib] -= kb * du[0]; B->vy[ib] -= kb * du[1]; B->vz[ib] -= kb * du[2];
+                    double va[3] = {A->vx[ia] + ka * du[0], A->vy[ia] + ka * du[1], A->vz[ia] + ka * du[2]};
+                    double vb[3] = {B->vx[ib] - kb * du[0], B->vy[ib] - kb * du[1], B->vz[ib] - kb * du[2]};
+                    collided_units(A, sa, ia, va, ncoll, spl, nspl);
+                    collided_units(B, sb, ib, vb, ncoll, spl, nspl);
                     event_add(o, 1, A->id[ia], B->id[ib]);
+                    o->n_kind_w[1] += ncoll;
                 } else if (cls == 1) {
                     /* Impact ionization Cu + e -> Cu+ + 2e (Table colls). Reading
                      * (the paper defers details to its references): in the rest
@@ -749,24 +821,26 @@ static void mcc_class(const orc_config* c, uint32_t step, int cls, const entry* 
                     double e1 = u5 * erem, e2 = erem - e1;
                     double w1 = sqrt(2.0 * e1 * E_CH / M_EL), w2 = sqrt(2.0 * e2 * E_CH / M_EL);
                     double vn[3] = {B->vx[ib] * h / dt, B->vy[ib] * h / dt, B->vz[ib] * h / dt};
-                    A->vx[ia] = (vn[0] + w1 * s1v[0]) * dt / h;
-                    A->vy[ia] = (vn[1] + w1 * s1v[1]) * dt / h;
-                    A->vz[ia] = (vn[2] + w1 * s1v[2]) * dt / h;
+                    double v1[3] = {(vn[0] + w1 * s1v[0]) * dt / h, (vn[1] + w1 * s1v[1]) * dt / h,
+                                    (vn[2] + w1 * s1v[2]) * dt / h};
+                    collided_units(A, sa, ia, v1, ncoll, spl, nspl);
                     product* pr = &prod[(*nprod)++];
-                    pr->kind = 0; pr->nid = B->id[ib]; pr->nidx = ib;
+                    pr->kind = 0; pr->nid = B->id[ib]; pr->nidx = ib; pr->c = ncoll;
                     pr->ve[0] = (vn[0] + w2 * s2v[0]) * dt / h;
                     pr->ve[1] = (vn[1] + w2 * s2v[1]) * dt / h;
                     pr->ve[2] = (vn[2] + w2 * s2v[2]) * dt / h;
                     pr->ev = event_add(o, 2, A->id[ia], B->id[ib]);
+                    o->n_kind_w[2] += ncoll;
                 } else {
                     /* Charge exchange Cu+ + Cu -> Cu + Cu+ (Table colls): the
                      * fast ion becomes a fast neutral and vice versa, i.e. the
                      * two velocities are exchanged while ids stay put. */
-                    double t;
-                    t = A->vx[ia]; A->vx[ia] = B->vx[ib]; B->vx[ib] = t;
-                    t = A->vy[ia]; A->vy[ia] = B->vy[ib]; B->vy[ib] = t;
-                    t = A->vz[ia]; A->vz[ia] = B->vz[ib]; B->vz[ib] = t;
+                    double va[3] = {B->vx[ib], B->vy[ib], B->vz[ib]};
+                    double vb[3] = {A->vx[ia], A->vy[ia], A->vz[ia]};
+                    collided_units(A, sa, ia, va, ncoll, spl, nspl);
+                    collided_units(B, sb, ib, vb, ncoll, spl, nspl);
                     event_add(o, 3, A->id[ia], B->id[ib]);
+                    o->n_kind_w[3] += ncoll;
                 }
             }
         }
@@ -778,7 +852,10 @@ static void mcc_class(const orc_config* c, uint32_t step, int cls, const entry* 
  * pairs, then field ionization of every neutral without an event, then the
  * products. Ionization products (impact and field) are created in the order
  * (impact before field, ascending neutral id), each taking two new ids: the ion
- * first, then the electron. Ionized neutrals are removed (order preserved). */
+ * first, then the electron; each carries the N_coll ionized units, which the
+ * neutral loses. Then the split-off superparticles, in the order (species,
+ * parent id), each taking one new id. Neutrals left without weight are
+ * removed (order preserved). */
 int orc_collide(const orc_config* c, uint32_t step, int32_t flags, const double* E,
                 orc_species* sp, uint32_t* next_id, orc_collide_out* o) {
     int64_t ne = sp[0].n + sp[1].n + sp[2].n;
@@ -794,11 +871,13 @@ int orc_collide(const orc_config* c, uint32_t step, int32_t flags, const double*
     for (int s = 0; s < 3; ++s) used[s] = calloc(sp[s].n + 1, 1);
     product* prod = malloc((sp[2].n + 1) * sizeof(product));
     int64_t nprod = 0;
-    o->n_ev = 0; o->n_fragile = 0; o->n_bsi_skip = 0;
-    for (int k = 0; k < 5; ++k) o->n_kind[k] = 0;
+    split* spl = malloc((ne + 1) * sizeof(split));
+    int64_t nspl = 0;
+    o->n_ev = 0; o->n_fragile = 0; o->n_bsi_skip = 0; o->n_split = 0;
+    for (int k = 0; k < 5; ++k) { o->n_kind[k] = 0; o->n_kind_w[k] = 0; }
 
-    if (flags & ORC_COLL_MCC1) mcc_class(c, step, 1, ent, ne, sp, used, prod, &nprod, o);
-    if (flags & ORC_COLL_MCC2) mcc_class(c, step, 2, ent, ne, sp, used, prod, &nprod, o);
+    if (flags & ORC_COLL_MCC1) mcc_class(c, step, 1, ent, ne, sp, used, prod, &nprod, spl, &nspl, o);
+    if (flags & ORC_COLL_MCC2) mcc_class(c, step, 2, ent, ne, sp, used, prod, &nprod, spl, &nspl, o);
 
     if (flags & ORC_COLL_FI) {
         /* Field ionization (Sec. 2.3.4): a neutral ionizes in the step when
@@ -820,21 +899,36 @@ int orc_collide(const orc_config* c, uint32_t step, int32_t flags, const double*
             double U, unused;
             draw2(c, N->id[p], step, TAG_FI, 0, &U, &unused);
             if (pdt > 0.0 && fabs(U - pdt) <= FRAGILE_FI * pdt) fragile_add(o, N->id[p]);
-            if (pdt > U) {
+            /* a neutral superparticle of weight w: each of its w units ionizes
+             * when P dt > U_i (U_0 above, U_i from (id, step, FI + 16, i)) */
+            uint32_t ncoll = (pdt > U) ? 1u : 0u;
+            for (uint32_t q = 1; q < wgt(N, p); ++q) {
+                double Uq, unq;
+                draw2(c, N->id[p], step, TAG_FI + TAG_SUB, q, &Uq, &unq);
+                if (pdt > 0.0 && fabs(Uq - pdt) <= FRAGILE_FI * pdt) fragile_add(o, N->id[p]);
+                if (pdt > Uq) ++ncoll;
+            }
+            if (ncoll > 0) {
                 used[ORC_SP_NEU][p] = 1;
                 product* pr = &prod[nprod++];
-                pr->kind = 1; pr->nid = N->id[p]; pr->nidx = p;
+                pr->kind = 1; pr->nid = N->id[p]; pr->nidx = p; pr->c = ncoll;
                 pr->ve[0] = N->vx[p]; pr->ve[1] = N->vy[p]; pr->ve[2] = N->vz[p];
                 pr->ev = event_add(o, 4, UINT32_MAX, N->id[p]);
+                o->n_kind_w[4] += ncoll;
             }
         }
     }
 
     int rc = 0;
     qsort(prod, nprod, sizeof(product), product_cmp);
+    qsort(spl, nspl, sizeof(split), split_cmp);
     orc_species* I = &sp[ORC_SP_ION]; orc_species* El = &sp[ORC_SP_E]; orc_species* N = &sp[ORC_SP_NEU];
-    if (!grow_ok(I, nprod) || !grow_ok(El, nprod)) rc = -1;
-    uint8_t* dead = calloc(N->n + 1, 1);
+    int64_t nsp_new[3] = {0, 0, 0};
+    for (int64_t k = 0; k < nspl; ++k) nsp_new[spl[k].sp]++;
+    if (!grow_ok(I, nprod + nsp_new[ORC_SP_ION]) || !grow_ok(El, nprod + nsp_new[ORC_SP_E]) ||
+        !grow_ok(N, nsp_new[ORC_SP_NEU]))
+        rc = -1;
+    uint8_t* dead = calloc(N->n + nsp_new[ORC_SP_NEU] + 1, 1);
     for (int64_t k = 0; k < nprod && rc == 0; ++k) {
         product* pr = &prod[k];
         int64_t ni = pr->nidx;
@@ -843,31 +937,47 @@ int orc_collide(const orc_config* c, uint32_t step, int32_t flags, const double*
         I->x[a] = N->x[ni]; I->y[a] = N->y[ni]; I->z[a] = N->z[ni];
         I->vx[a] = N->vx[ni]; I->vy[a] = N->vy[ni]; I->vz[a] = N->vz[ni];
         I->id[a] = id_ion;
+        if (I->w) I->w[a] = pr->c;
         int64_t b = El->n++;
         El->x[b] = N->x[ni]; El->y[b] = N->y[ni]; El->z[b] = N->z[ni];
         El->vx[b] = pr->ve[0]; El->vy[b] = pr->ve[1]; El->vz[b] = pr->ve[2];
         El->id[b] = id_e;
-        dead[ni] = 1;
+        if (El->w) El->w[b] = pr->c;
+        if (N->w && N->w[ni] > pr->c) N->w[ni] -= pr->c;
+        else dead[ni] = 1;
         if (pr->ev < o->ev_cap) { o->ev[pr->ev].new_ion = id_ion; o->ev[pr->ev].new_e = id_e; }
     }
-    /* remove the ionized neutrals, keeping the order of the others */
+    /* split-off superparticles at their parents' positions */
+    for (int64_t k = 0; k < nspl && rc == 0; ++k) {
+        split* q = &spl[k];
+        orc_species* S = &sp[q->sp];
+        int64_t a = S->n++;
+        S->x[a] = S->x[q->pidx]; S->y[a] = S->y[q->pidx]; S->z[a] = S->z[q->pidx];
+        S->vx[a] = q->v[0]; S->vy[a] = q->v[1]; S->vz[a] = q->v[2];
+        S->id[a] = (*next_id)++;
+        S->w[a] = q->c;
+        S->w[q->pidx] -= q->c;
+    }
+    o->n_split = nspl;
+    /* remove the neutrals left without weight, keeping the order of the others */
     int64_t w = 0;
     for (int64_t p = 0; p < N->n; ++p) {
         if (dead[p]) continue;
         N->x[w] = N->x[p]; N->y[w] = N->y[p]; N->z[w] = N->z[p];
         N->vx[w] = N->vx[p]; N->vy[w] = N->vy[p]; N->vz[w] = N->vz[p];
         N->id[w] = N->id[p];
+        if (N->w) N->w[w] = N->w[p];
         ++w;
     }
     N->n = w;
-    free(dead); free(prod); free(ent);
+    free(dead); free(prod); free(spl); free(ent);
     for (int s = 0; s < 3; ++s) free(used[s]);
     return rc;
 }
 
 /* ------------------------------------------------------------------------ */
 /* Moments: kinetic energy per species [J], the Shockley-Ramo gap current
- * I = sum q v . E0(r) [A] with E0 the field of the unit-anode Laplace problem
+ * I = sum w q v . E0(r) [A] (w the superparticle weight) with E0 the field of the unit-anode Laplace problem
  * (Sec. 2.3.1), evaluated on the stored state (positions x^{n+1}, velocities
  * v^{n+1/2}), and the particle counts. out = {KE_e, KE_ion, KE_neu, I_SR,
  * n_e, n_ion, n_neu, 0}. */
@@ -880,11 +990,12 @@ void orc_moments(const orc_config* c, const orc_species* sp, const double* E0, d
         double ke = 0.0;
         for (int64_t p = 0; p < sp[s].n; ++p) {
             double vx = sp[s].vx[p] * sv, vy = sp[s].vy[p] * sv, vz = sp[s].vz[p] * sv;
-            ke += 0.5 * mass[s] * (vx * vx + vy * vy + vz * vz);
+            double wp = (double)wgt(&sp[s], p);
+            ke += wp * 0.5 * mass[s] * (vx * vx + vy * vy + vz * vz);
             if (charge[s] != 0.0) {
                 double e[3];
                 orc_gather(c, E0, sp[s].x[p], sp[s].y[p], sp[s].z[p], e);
-                isr += charge[s] * (vx * e[0] + vy * e[1] + vz * e[2]);
+                isr += wp * charge[s] * (vx * e[0] + vy * e[1] + vz * e[2]);
             }
         }
         out[s] = ke;

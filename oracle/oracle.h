@@ -34,12 +34,18 @@ typedef struct orc_config {
     uint64_t seed;       /* Philox key */
     int32_t fn_rings;    /* cap rings of emission patches */
     int32_t fn_az;       /* azimuthal patches per ring */
+    int32_t w_max;       /* largest superparticle weight of evaporated neutrals (<= 1: all weights 1) */
+    int32_t pad;
+    double n_max;        /* SP number density [1/m^3] above which evaporated neutrals get heavier */
 } orc_config;
 
+/* Superparticle weights (Sec. 2.3.2): w[p] physical particles per SP, in
+ * units of the smallest weight w_min = 1 (NULL: every weight is 1). */
 typedef struct orc_species {
     int64_t n, cap;
     double *x, *y, *z, *vx, *vy, *vz;
     uint32_t* id;
+    uint32_t* w;
 } orc_species;
 
 typedef struct orc_event {
@@ -54,6 +60,8 @@ typedef struct orc_collide_out {
     uint32_t* fragile; int64_t fr_cap, n_fragile;
     int64_t n_kind[5];
     int64_t n_bsi_skip;     /* neutrals above the barrier-suppression limit */
+    int64_t n_kind_w[5];    /* physical collisions per kind (sum of N_coll over the events) */
+    int64_t n_split;        /* superparticles split off by partial collisions */
 } orc_collide_out;
 
 enum { ORC_SP_E = 0, ORC_SP_ION = 1, ORC_SP_NEU = 2 };
@@ -93,7 +101,7 @@ int64_t orc_fn_inject(const orc_config* c, uint32_t step, const double* phi, orc
 
 double orc_evap_flux(const orc_config* c, double T);
 int64_t orc_evaporate(const orc_config* c, uint32_t step, double T, orc_species* nsp, uint32_t* next_id,
-                      double* n_expected);
+                      double* n_expected, const int64_t* cell_count);
 
 int orc_collide(const orc_config* c, uint32_t step, int32_t flags, const double* E,
                 orc_species* sp, uint32_t* next_id, orc_collide_out* out);

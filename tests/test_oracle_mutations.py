@@ -9,6 +9,7 @@ import pytest
 import oracle
 import test_oracle_readings as R
 import test_oracle_surface as S
+import test_oracle_weights as WT
 
 _SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
 
@@ -37,10 +38,11 @@ MUTATIONS = [
     ("no impact exclusion in field ionization",
      "if (used[ORC_SP_NEU][p]) continue;", "", R.pin_priority),
     ("(Cu+,Cu) before (e,Cu)",
-     "    if (flags & ORC_COLL_MCC1) mcc_class(c, step, 1, ent, ne, sp, used, prod, &nprod, o);\n"
-     "    if (flags & ORC_COLL_MCC2) mcc_class(c, step, 2, ent, ne, sp, used, prod, &nprod, o);",
-     "    if (flags & ORC_COLL_MCC2) mcc_class(c, step, 2, ent, ne, sp, used, prod, &nprod, o);\n"
-     "    if (flags & ORC_COLL_MCC1) mcc_class(c, step, 1, ent, ne, sp, used, prod, &nprod, o);", R.pin_priority),
+     "    if (flags & ORC_COLL_MCC1) mcc_class(c, step, 1, ent, ne, sp, used, prod, &nprod, spl, &nspl, o);\n"
+     "    if (flags & ORC_COLL_MCC2) mcc_class(c, step, 2, ent, ne, sp, used, prod, &nprod, spl, &nspl, o);",
+     "    if (flags & ORC_COLL_MCC2) mcc_class(c, step, 2, ent, ne, sp, used, prod, &nprod, spl, &nspl, o);\n"
+     "    if (flags & ORC_COLL_MCC1) mcc_class(c, step, 1, ent, ne, sp, used, prod, &nprod, spl, &nspl, o);",
+     R.pin_priority),
     ("emission field half a spacing out",
      "g[0] + g[3], g[1] + g[4], g[2] + g[5]) / h;",
      "g[0] + 0.5 * g[3], g[1] + 0.5 * g[4], g[2] + 0.5 * g[5]) / (0.5 * h);", R.pin_emission_field_point),
@@ -57,6 +59,18 @@ MUTATIONS = [
     ("Shockley-Ramo current from the field instead of the weighting field",
      "orc_gather(c, E0, s->x[p], s->y[p], s->z[p], w);", "orc_gather(c, E, s->x[p], s->y[p], s->z[p], w);",
      S.pin_shockley_ramo_push),
+    ("collision probability without the target weight",
+     "double P = -expm1(-um * n * (double)wt * stot * dt);", "double P = -expm1(-um * n * 1.0 * stot * dt);",
+     WT.pin_ncoll_binomial),
+    ("the lighter superparticle as the target",
+     "uint32_t wt = wa > wb ? wa : wb, npart = wa < wb ? wa : wb;",
+     "uint32_t wt = wa < wb ? wa : wb, npart = wa < wb ? wa : wb;", WT.pin_ncoll_binomial),
+    ("one field-ionization draw per neutral superparticle",
+     "for (uint32_t q = 1; q < wgt(N, p); ++q) {", "for (uint32_t q = 1; q < 1u; ++q) {",
+     WT.pin_weighted_field_ionization),
+    ("injection weight without the geometric mean",
+     "double r = sqrt(n_cell / c->n_max * (double)n_inj);", "double r = n_cell / c->n_max * (double)n_inj;",
+     WT.pin_injection_weights),
 ]
 
 
