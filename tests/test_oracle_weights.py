@@ -149,7 +149,7 @@ def pin_injection_weights():
     cfg.surface_T = 3200.0
     cfg.dt = 4e-10              # hundreds of atoms per patch and step; nothing moves here
     cfg.fn_rings, cfg.fn_az = 1, 1
-    cfg.w_max, cfg.n_max = 40, 1e24
+    cfg.w_max, cfg.n_max = 40, 1e28     # weights between 1 and w_max for these counts
     o = oracle.Oracle(cfg, laplace=False)
     rng = np.random.default_rng(64)
     o.cell_count = rng.integers(0, 60, size=o.cell_count.size).astype(np.int64)
