@@ -596,6 +596,7 @@ def learned_experiment(args, log):
     and of MG-PCG from a zero guess, the previous step's potential, V0 phi1
     and the learned guess (projected, judged by plain CG)."""
     import dataclasses
+    import numpy as np
     import torch
     from paper_2402_08404_amd import pic, warmstart
     from paper_2402_08404_amd import workloads as W
