@@ -124,6 +124,12 @@ typedef struct pic_config {
                               evaporation of neutrals in the inject phase (0: no evaporation) */
     double circuit_R;      /* series resistance [ohm] of the RC circuit (0: the anode stays at V0) */
     double circuit_C;      /* gap capacitance [F] of the RC circuit */
+    /* Superparticle weights (Sec. 2.3.2): */
+    int32_t weighted;      /* 1: every superparticle carries an integer weight (pic_buffers.w; physical
+                              particles per superparticle, the smallest weight w_min being 1); collisions
+                              split superparticles; 0: every weight is 1 and no weight array is read */
+    int32_t w_max;         /* largest weight given to evaporated neutrals by the injection rule (<= 1: 1) */
+    double n_max;          /* superparticle density [1/m^3] of the injection rule (1e24 = 1e-6 per A^3) */
 } pic_config;
 
 typedef struct pic_buffers {
@@ -145,6 +151,7 @@ typedef struct pic_buffers {
     uint8_t* node_type;    /* nx*ny*nz: 0 free, 1 held at 0 V, 2 held at V0 */
     void* scratch;         /* work memory of pic_scratch_size bytes, 256-byte aligned */
     size_t scratch_bytes;
+    uint32_t* w[3];        /* with cfg.weighted: the weight of every slot per species (capacity cap[s]) */
 } pic_buffers;
 
 typedef struct pic_particles {
@@ -152,6 +159,7 @@ typedef struct pic_particles {
     int32_t pad;
     int64_t n;
     const void *x, *y, *z, *vx, *vy, *vz;  /* device arrays of n elements, same type as the state */
+    const uint32_t* w;     /* device weights of the n particles (NULL: weight 1); read with cfg.weighted */
 } pic_particles;
 
 typedef struct pic_solve_info {
@@ -193,6 +201,11 @@ typedef struct pic_moments_t {
     double v_gap;              /* gap voltage = anode potential [V] (V0 without the circuit) */
     double i_gap;              /* Shockley-Ramo current of the last push [A] (circuit only) */
     double i_tot;              /* circuit current (V0 - V_gap) / R of the last circuit step [A] */
+    /* superparticle weights */
+    int64_t n_phys[3];         /* physical particles per species (sum of the weights of the alive) */
+    int64_t events_w[5];       /* cumulative physical collisions per event kind (sum of N_coll) */
+    int64_t splits;            /* cumulative superparticles split off by partial collisions */
+    int64_t evap_atoms;        /* cumulative evaporated atoms (the weights of the evaporated neutrals) */
 } pic_moments_t;
 
 typedef struct pic_event {

@@ -42,6 +42,7 @@ struct PushArgs {
     double* dpart;   // per-block FP64 partials: [block][4] = sum |V|^2 of ions reaching the cathode plane and
                      // the tip, sum V . E0 (the Shockley-Ramo current before its factor)
     const typename V4<T>::type* field0;  // weighting field (with the circuit only, else null)
+    uint32_t* fi_cnt;  // weighted runs: field-ionized units of each candidate neutral
     double fi_thr, ebsi, adk_c, adk_e, x32, dt_fs;
 };
 
@@ -113,7 +114,9 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs<T> a) {
                     // the weighting field at x^n with v^{n+1/2}
                     T wx, wy, wz;
                     gather<T>(g, a.field0, X, Y, Z, wx, wy, wz);
-                    if (alive) sr += (double)VX * (double)wx + (double)VY * (double)wy + (double)VZ * (double)wz;
+                    if (alive)
+                        sr += (a.s.w ? (double)a.s.w[il] : 1.0) *
+                              ((double)VX * (double)wx + (double)VY * (double)wy + (double)VZ * (double)wz);
                 }
             }
             X += VX;
@@ -148,7 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs<T> a) {
             lost[code]++;
             if (SP == PIC_ION && MOVE && (code == 1 || code == 4)) {
                 const double vx = (double)VX, vy = (double)VY, vz = (double)VZ;
-                bomb[code == 1 ? 0 : 1] += vx * vx + vy * vy + vz * vz;
+                bomb[code == 1 ? 0 : 1] += (a.s.w ? (double)a.s.w[i] : 1.0) * (vx * vx + vy * vy + vz * vz);
             }
             continue;
         }
@@ -168,7 +171,13 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs<T> a) {
             } else if (Eg > a.fi_thr) {
                 double pdt = a.adk_c * pow(20.5 * a.x32 / Eg, a.adk_e) * exp(-6.83 * a.x32 / Eg) * a.dt_fs;
                 Draw2 u = draw2(a.seed, id, a.step, kTagFi, 0);
-                cand = pdt > u.a;
+                uint32_t nc = (pdt > u.a) ? 1u : 0u;
+                // every unit of a weighted neutral draws for itself (Sec. 2.3.2)
+                const uint32_t wn = a.s.w ? a.s.w[i] : 1u;
+                for (uint32_t q = 1; q < wn; ++q)
+                    nc += (pdt > draw2(a.seed, id, a.step, kTagFi + kTagSub, q).a) ? 1u : 0u;
+                cand = nc > 0;
+                if (cand && a.fi_cnt) a.fi_cnt[i] = nc;
             }
             unsigned long long p = wave_append(&a.st->n_fi, cand);
             if (cand) a.fi_list[p] = (uint32_t)i;
@@ -347,7 +356,8 @@ __global__ __launch_bounds__(kBlock) void k_deposit_tiles(DepositArgs<T> a) {
         int ci = clampi((int)floor(X), 0, g.nx - 2), cj = clampi((int)floor(Y), 0, g.ny - 2),
             ck = clampi((int)floor(Z), 0, g.nz - 2);
         int64_t qx = quantize(X - ci, 13), qy = quantize(Y - cj, 13), qz = quantize(Z - ck, 14);
-        int64_t sg = s == PIC_ELECTRON ? -1 : 1;
+        // a superparticle of weight w carries w charges
+        int64_t sg = (s == PIC_ELECTRON ? -1 : 1) * (P.w ? (int64_t)P.w[i] : 1);
         int64_t w[2][3] = {{8192 - qx, 8192 - qy, 16384 - qz}, {qx, qy, qz}};
         int lx = ci - ox, ly = cj - oy, lz = ck - oz;
 #pragma unroll
@@ -411,7 +421,40 @@ struct MccArgs {
     pic_event* ev;
     int64_t ev_cap;
     int record, write_sorted;
+    // superparticle weights (weighted runs only)
+    int weighted;
+    uint32_t* prod_c;         // per neutral slot: ionized units of its product
+    uint32_t* fi_cnt;         // per neutral slot: field-ionized units (from the push)
+    uint32_t* split_list[3];  // per species: parent slots of the split-offs
+    uint32_t* split_c[3];     // per species and slot: units split off
+    double* split_v[3];       // per species and slot: their velocity
+    uint32_t* split_bm[3];    // per species: parents as a bitmap over ids
 };
+
+// The c collided units of superparticle p of species sp take the velocity
+// v (grid units): in place when they are the whole superparticle, else they
+// are split off (Sec. 2.3.2) as a new superparticle made in the products
+// phase in the order (species, parent id); the parent keeps the rest and its
+// velocity.
+template <typename T>
+__device__ inline void collided_units(const MccArgs<T>& a, const Species<T>& S, int sp, uint32_t p, const double v[3],
+                                      uint32_t c) {
+    const uint32_t w = S.w ? S.w[p] : 1u;
+    if (c >= w) {
+        S.vx[p] = (T)v[0];
+        S.vy[p] = (T)v[1];
+        S.vz[p] = (T)v[2];
+        return;
+    }
+    const unsigned long long q = atomicAdd(&a.st->n_split[sp], 1ull);
+    a.split_list[sp][q] = p;
+    a.split_c[sp][p] = c;
+    a.split_v[sp][3 * (int64_t)p + 0] = v[0];
+    a.split_v[sp][3 * (int64_t)p + 1] = v[1];
+    a.split_v[sp][3 * (int64_t)p + 2] = v[2];
+    const uint32_t id = S.id[p];
+    atomicOr(&a.split_bm[sp][id >> 5], 1u << (id & 31));
+}
 
 // Linear index of the cell with this key: the per-cell draw is keyed by it.
 __device__ inline uint32_t linear_cell(const Grid& g, uint32_t key) {
@@ -457,14 +500,20 @@ __device__ inline int64_t record_event(const MccArgs<T>& a, int kind, uint32_t i
 
 // Decide and apply one pair of class cls (1: e-Cu, 2: Cu+-Cu). ia indexes the
 // charged particle, ib the neutral; pid is the projectile id. Returns the
-// event kind, or 0.
+// event kind, or 0; nc receives N_coll, the collided units (Sec. 2.3.2: the
+// lighter superparticle is cut into min(w_a, w_b) sub-particles, each
+// colliding with the heavier one with P = 1 - exp(-u n w_t sigma dt); with
+// every weight 1 this is one binary collision).
 template <typename T>
 __device__ int resolve_pair(const MccArgs<T>& a, int cls, uint32_t pid, uint32_t ia, uint32_t ib, int NT,
-                            double pnull) {
-    Draw2 d = draw2(a.seed, pid, a.step, cls == 1 ? kTagMcc1 : kTagMcc2, 0);
-    if (d.a >= pnull) return 0;  // null collision
+                            double pnull, uint32_t& nc) {
+    const uint32_t tag = cls == 1 ? kTagMcc1 : kTagMcc2;
+    Draw2 d = draw2(a.seed, pid, a.step, tag, 0);
+    if (d.a >= pnull) return 0;  // null collision (pnull is 2 in weighted runs)
     const Species<T>& A = a.sp[cls == 1 ? PIC_ELECTRON : PIC_ION];
     const Species<T>& B = a.sp[PIC_NEUTRAL];
+    const uint32_t wa = A.w ? A.w[ia] : 1u, wb = B.w ? B.w[ib] : 1u;
+    const uint32_t wt = wa > wb ? wa : wb, npart = wa < wb ? wa : wb;
     double s = a.h / a.dt;
     double vA[3] = {(double)A.vx[ia], (double)A.vy[ia], (double)A.vz[ia]};
     double vB[3] = {(double)B.vx[ib], (double)B.vy[ib], (double)B.vz[ib]};
@@ -481,18 +530,17 @@ __device__ int resolve_pair(const MccArgs<T>& a, int cls, uint32_t pid, uint32_t
     }
     double stot = sig0 + sig1;
     double n = (double)NT / (a.h * a.h * a.h);
-    double P = -expm1(-um * n * stot * a.dt);
-    if (!(d.a < P)) return 0;
+    double P = -expm1(-um * n * (double)wt * stot * a.dt);
+    uint32_t ncoll = (d.a < P) ? 1u : 0u;
+    for (uint32_t q = 1; q < npart; ++q) ncoll += (draw2(a.seed, pid, a.step, tag + kTagSub, q).a < P) ? 1u : 0u;
+    nc = ncoll;
+    if (ncoll == 0) return 0;
     uint32_t idA = A.id[ia], idB = B.id[ib];
     if (cls == 2) {
-        // charge exchange: the two velocities are exchanged
-        T tx = A.vx[ia], ty = A.vy[ia], tz = A.vz[ia];
-        A.vx[ia] = B.vx[ib];
-        A.vy[ia] = B.vy[ib];
-        A.vz[ia] = B.vz[ib];
-        B.vx[ib] = tx;
-        B.vy[ib] = ty;
-        B.vz[ib] = tz;
+        // charge exchange: the collided units exchange their velocities
+        const double na[3] = {vB[0], vB[1], vB[2]}, nb[3] = {vA[0], vA[1], vA[2]};
+        collided_units(a, A, PIC_ION, ia, na, ncoll);
+        collided_units(a, B, PIC_NEUTRAL, ib, nb, ncoll);
         record_event(a, PIC_EV_CX, idA, idB);
         return PIC_EV_CX;
     }
@@ -518,19 +566,19 @@ __device__ int resolve_pair(const MccArgs<T>& a, int cls, uint32_t pid, uint32_t
         double du2 = -st * w0 + ct * w2;
         double mu = mA * a.m_ion / (mA + a.m_ion);
         double ka = mu / mA * g, kb = mu / a.m_ion * g;
-        A.vx[ia] = (T)(vA[0] + ka * du0);
-        A.vy[ia] = (T)(vA[1] + ka * du1);
-        A.vz[ia] = (T)(vA[2] + ka * du2);
-        B.vx[ib] = (T)(vB[0] - kb * du0);
-        B.vy[ib] = (T)(vB[1] - kb * du1);
-        B.vz[ib] = (T)(vB[2] - kb * du2);
+        const double na[3] = {vA[0] + ka * du0, vA[1] + ka * du1, vA[2] + ka * du2};
+        const double nb[3] = {vB[0] - kb * du0, vB[1] - kb * du1, vB[2] - kb * du2};
+        collided_units(a, A, PIC_ELECTRON, ia, na, ncoll);
+        collided_units(a, B, PIC_NEUTRAL, ib, nb, ncoll);
         record_event(a, PIC_EV_ELASTIC, idA, idB);
         return PIC_EV_ELASTIC;
     }
     // Impact ionization Cu + e -> Cu+ + 2e: in the rest frame of the neutral
     // the energy above xi is shared as U5 : 1 - U5 by the scattered and the
     // new electron, both leaving isotropically; the ion keeps the neutral's
-    // position and velocity, the new electron starts at that position.
+    // position and velocity, the new electron starts at that position. The
+    // ion and the new electron carry the ionized units, which the neutral
+    // loses in the products phase.
     Draw2 r1 = draw2(a.seed, pid, a.step, kTagMcc1, 1);
     Draw2 r2 = draw2(a.seed, pid, a.step, kTagMcc1, 2);
     Draw2 r3 = draw2(a.seed, pid, a.step, kTagMcc1, 3);
@@ -541,12 +589,12 @@ __device__ int resolve_pair(const MccArgs<T>& a, int cls, uint32_t pid, uint32_t
     double e1 = r3.a * erem, e2 = erem - e1;
     double w1 = sqrt(2.0 * e1 * kQe / kMe), w2 = sqrt(2.0 * e2 * kQe / kMe);
     double vn[3] = {vB[0] * s, vB[1] * s, vB[2] * s};
-    A.vx[ia] = (T)((vn[0] + w1 * s1[0]) * g);
-    A.vy[ia] = (T)((vn[1] + w1 * s1[1]) * g);
-    A.vz[ia] = (T)((vn[2] + w1 * s1[2]) * g);
+    const double v1[3] = {(vn[0] + w1 * s1[0]) * g, (vn[1] + w1 * s1[1]) * g, (vn[2] + w1 * s1[2]) * g};
+    collided_units(a, A, PIC_ELECTRON, ia, v1, ncoll);
     a.prod_ve[3 * (int64_t)ib + 0] = (vn[0] + w2 * s2[0]) * g;
     a.prod_ve[3 * (int64_t)ib + 1] = (vn[1] + w2 * s2[1]) * g;
     a.prod_ve[3 * (int64_t)ib + 2] = (vn[2] + w2 * s2[2]) * g;
+    if (a.prod_c) a.prod_c[ib] = ncoll;
     atomicOr(&a.bitmap_imp[idB >> 5], 1u << (idB & 31));
     unsigned long long p = wave_append(&a.st->n_prod, true);
     a.prod_list[p] = ib;  // kind 0 (impact); n_prod_kind[0] is added per block
@@ -562,6 +610,9 @@ __device__ int resolve_pair(const MccArgs<T>& a, int cls, uint32_t pid, uint32_t
 // sigma is the last value).
 template <typename T>
 __device__ inline double pnull_of(const MccArgs<T>& a, int cls, int NT) {
+    // weighted pairs collide with more than one draw and a weighted target
+    // probability: no null-collision bound, every pair is decided in full
+    if (a.weighted) return 2.0;
     const int sa = cls == 1 ? PIC_ELECTRON : PIC_ION;
     const double ug = ((double)__uint_as_float(a.st->smax_bits[sa]) + (double)__uint_as_float(a.st->smax_bits[2])) *
                       (1.0 + 0x1p-20);
@@ -590,7 +641,7 @@ __device__ inline double pnull_of(const MccArgs<T>& a, int cls, int NT) {
 // compute it.
 template <typename T>
 __device__ void cell_class_seq(const MccArgs<T>& a, int cls, uint32_t cell, const uint64_t* kk, const uint32_t* ee,
-                               int a0, int na, int b0, int nb, uint32_t& used, int cnt[5], const double* pn = nullptr) {
+                               int a0, int na, int b0, int nb, uint32_t& used, int cnt[10], const double* pn = nullptr) {
     if (na == 0 || nb == 0) return;
     bool a_proj = na <= nb;
     int P0 = a_proj ? a0 : b0, NP = a_proj ? na : nb;
@@ -609,17 +660,19 @@ __device__ void cell_class_seq(const MccArgs<T>& a, int cls, uint32_t cell, cons
         int brank = bi - b0;
         if (cls == 2 && ((used >> brank) & 1u)) continue;
         uint32_t pid = (uint32_t)(kk[pi] & 0xFFFFFFFFu);
-        int kind = resolve_pair(a, cls, pid, ee[ai] & 0x3FFFFFFFu, ee[bi] & 0x3FFFFFFFu, NT, pnull);
+        uint32_t nc = 0;
+        int kind = resolve_pair(a, cls, pid, ee[ai] & 0x3FFFFFFFu, ee[bi] & 0x3FFFFFFFu, NT, pnull, nc);
         if (kind) {
             used |= 1u << brank;
             a.nflag[ee[bi] & 0x3FFFFFFFu] = a.step + 1u;
             cnt[kind]++;
+            cnt[5 + kind] += (int)nc;
         }
     }
 }
 
 template <typename T>
-__device__ inline void flush_counts(DevState* st, int cnt[5]) {
+__device__ inline void flush_counts(DevState* st, int cnt[10]) {
     __shared__ int sh[kBlock / 64];
     for (int k = 1; k <= 3; ++k) {
         int t = block_sum(cnt[k], sh);
@@ -627,13 +680,15 @@ __device__ inline void flush_counts(DevState* st, int cnt[5]) {
             atomicAdd(&st->events[k], (unsigned long long)t);
             if (k == PIC_EV_IONIZE) atomicAdd(&st->n_prod_kind[0], (unsigned long long)t);
         }
+        int tw = block_sum(cnt[5 + k], sh);
+        if (threadIdx.x == 0 && tw) atomicAdd(&st->events_w[k], (unsigned long long)tw);
     }
 }
 
 // Collisions of one cell of 2 .. kSmallCell particles (one lane).
 template <typename T>
 __device__ inline void mcc_cell(const MccArgs<T>& a, uint32_t c, uint32_t o0, int n, const double (*pn)[kSmallCell + 1],
-                                int cnt[5]) {
+                                int cnt[10]) {
     uint64_t kk[kSmallCell];
     uint32_t ee[kSmallCell];
     for (int t = 0; t < n; ++t) {
@@ -820,7 +875,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_mcc_cells(MccArgs<T> a) {
     __shared__ double pn[2][kSmallCell + 1];
     pnull_table(a, pn);
-    int cnt[5] = {0, 0, 0, 0, 0};
+    int cnt[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t nl = (int64_t)*a.mcc_total;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nl; t += stride) {
@@ -838,7 +893,7 @@ __global__ __launch_bounds__(64) void k_mcc_big(MccArgs<T> a) {
     __shared__ uint64_t kk[kBigCell];
     __shared__ uint32_t ee[kBigCell];
     __shared__ uint8_t used[kBigCell];
-    int cnt[5] = {0, 0, 0, 0, 0};
+    int cnt[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int lane = threadIdx.x;
     const int64_t nbig = (int64_t)a.st->n_big;
     for (int64_t b = blockIdx.x; b < nbig; b += gridDim.x) {
@@ -910,11 +965,13 @@ __global__ __launch_bounds__(64) void k_mcc_big(MccArgs<T> a) {
                     int ai = a_proj ? pi : ti, bi = a_proj ? ti : pi;
                     if (cls == 2 && used[bi]) continue;
                     uint32_t pid = (uint32_t)(kk[pi] & 0xFFFFFFFFu);
-                    int kind = resolve_pair(a, cls, pid, ee[ai] & 0x3FFFFFFFu, ee[bi] & 0x3FFFFFFFu, NT, pnull);
+                    uint32_t nc = 0;
+                    int kind = resolve_pair(a, cls, pid, ee[ai] & 0x3FFFFFFFu, ee[bi] & 0x3FFFFFFFu, NT, pnull, nc);
                     if (kind) {
                         used[bi] = 1;
                         a.nflag[ee[bi] & 0x3FFFFFFFu] = a.step + 1u;
                         cnt[kind]++;
+                        cnt[5 + kind] += (int)nc;
                     }
                 }
             }
@@ -927,6 +984,8 @@ __global__ __launch_bounds__(64) void k_mcc_big(MccArgs<T> a) {
             atomicAdd(&a.st->events[k], (unsigned long long)t);
             if (k == PIC_EV_IONIZE) atomicAdd(&a.st->n_prod_kind[0], (unsigned long long)t);
         }
+        int tw = wave_sum(cnt[5 + k]);
+        if (lane == 0 && tw) atomicAdd(&a.st->events_w[k], (unsigned long long)tw);
     }
 }
 
@@ -934,7 +993,7 @@ __global__ __launch_bounds__(64) void k_mcc_big(MccArgs<T> a) {
 template <typename T>
 __global__ void k_fi_resolve(MccArgs<T> a, const uint32_t* fi_list, uint32_t* bitmap_fi) {
     int64_t n = (int64_t)a.st->n_fi;
-    int cnt = 0;
+    int cnt = 0, cntw = 0;
     const Species<T>& N = a.sp[PIC_NEUTRAL];
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
@@ -944,6 +1003,9 @@ __global__ void k_fi_resolve(MccArgs<T> a, const uint32_t* fi_list, uint32_t* bi
         if (!go) continue;
         a.nflag[ib] = a.step + 1u;
         uint32_t id = N.id[ib];
+        const uint32_t nc = a.fi_cnt ? a.fi_cnt[ib] : 1u;
+        if (a.prod_c) a.prod_c[ib] = nc;
+        cntw += (int)nc;
         atomicOr(&bitmap_fi[id >> 5], 1u << (id & 31));
         a.prod_ve[3 * (int64_t)ib + 0] = (double)N.vx[ib];
         a.prod_ve[3 * (int64_t)ib + 1] = (double)N.vy[ib];
@@ -958,6 +1020,8 @@ __global__ void k_fi_resolve(MccArgs<T> a, const uint32_t* fi_list, uint32_t* bi
         atomicAdd(&a.st->events[PIC_EV_FIELD_ION], (unsigned long long)t);
         atomicAdd(&a.st->n_prod_kind[1], (unsigned long long)t);
     }
+    int tw = block_sum(cntw, sh);
+    if (threadIdx.x == 0 && tw) atomicAdd(&a.st->events_w[PIC_EV_FIELD_ION], (unsigned long long)tw);
 }
 
 // ---------------------------------------------------------------------------
@@ -979,6 +1043,7 @@ struct ProdArgs {
     const uint32_t* prefix[2];
     pic_event* ev;
     int64_t ev_cap;
+    const uint32_t* prod_c;   // weighted runs: ionized units per neutral slot
 };
 
 template <typename T>
@@ -1019,6 +1084,10 @@ __global__ void k_products(ProdArgs<T> a) {
         El.vy[se] = (T)a.prod_ve[3 * (int64_t)ib + 1];
         El.vz[se] = (T)a.prod_ve[3 * (int64_t)ib + 2];
         El.id[se] = id_e;
+        if (a.prod_c) {
+            I.w[si] = a.prod_c[ib];
+            El.w[se] = a.prod_c[ib];
+        }
         int32_t q = a.prod_ev[ib];
         if (q >= 0 && q < a.ev_cap) {
             a.ev[q].new_ion = id_ion;
@@ -1039,8 +1108,85 @@ __global__ void k_products_clear(ProdArgs<T> a) {
         uint32_t ib = e & 0x7FFFFFFFu;
         uint32_t id = N.id[ib];
         atomicAnd(&a.bitmap[kind][id >> 5], ~(1u << (id & 31)));
-        N.id[ib] = kDead;
+        // the neutral loses the ionized units; without any left it is removed
+        if (a.prod_c && N.w[ib] > a.prod_c[ib]) N.w[ib] -= a.prod_c[ib];
+        else N.id[ib] = kDead;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Split-offs of partial collisions (Sec. 2.3.2): after the products, species
+// by species in the order (species, parent id): the rank of a split-off among
+// those of its species is read from the species' bitmap over parent ids and
+// its word prefix counts; it takes the slot n_slots + rank and the id
+// next_id + (split-offs of the species before) + rank, the parent's
+// position, the collided units and their velocity; the parent keeps the rest.
+
+template <typename T>
+struct SplitArgs {
+    Species<T> sp[3];
+    DevState* st;
+    uint32_t* list[3];
+    const uint32_t* c[3];
+    const double* v[3];
+    uint32_t* bm[3];
+    const uint32_t* pf[3];
+};
+
+template <typename T>
+__global__ void k_splits(SplitArgs<T> a, int s) {
+    const Species<T>& S = a.sp[s];
+    const int64_t n = (int64_t)a.st->n_split[s];
+    const int64_t base = (int64_t)a.st->n_slots[s];
+    if (base + n > S.cap) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicCAS(&a.st->error, 0, PIC_E_CAPACITY);
+        return;
+    }
+    unsigned long long before = 0;
+    for (int q = 0; q < s; ++q) before += a.st->n_split[q];
+    const uint32_t id0 = (uint32_t)(a.st->next_id + before);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+        const uint32_t p = a.list[s][q];
+        const uint32_t id = S.id[p];
+        const uint32_t wd = a.bm[s][id >> 5];
+        const int64_t r = (int64_t)a.pf[s][id >> 5] + __popc(wd & ((1u << (id & 31)) - 1u));
+        const int64_t m = base + r;
+        const uint32_t c = a.c[s][p];
+        S.x[m] = S.x[p];
+        S.y[m] = S.y[p];
+        S.z[m] = S.z[p];
+        S.vx[m] = (T)a.v[s][3 * (int64_t)p + 0];
+        S.vy[m] = (T)a.v[s][3 * (int64_t)p + 1];
+        S.vz[m] = (T)a.v[s][3 * (int64_t)p + 2];
+        S.id[m] = id0 + (uint32_t)r;
+        S.w[m] = c;
+        S.w[p] -= c;
+    }
+}
+
+// clear the parents' bits once every rank is taken
+template <typename T>
+__global__ void k_splits_clear(SplitArgs<T> a, int s) {
+    const Species<T>& S = a.sp[s];
+    const int64_t n = (int64_t)a.st->n_split[s];
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+        const uint32_t id = S.id[a.list[s][q]];
+        atomicAnd(&a.bm[s][id >> 5], ~(1u << (id & 31)));
+    }
+}
+
+__global__ void k_splits_finish(DevState* st, int64_t cap0, int64_t cap1, int64_t cap2) {
+    const int64_t cap[3] = {cap0, cap1, cap2};
+    unsigned long long tot = 0;
+    for (int s = 0; s < 3; ++s) {
+        if (st->n_slots[s] + st->n_split[s] > (unsigned long long)cap[s]) return;  // the error is set
+        tot += st->n_split[s];
+    }
+    for (int s = 0; s < 3; ++s) st->n_slots[s] += st->n_split[s];
+    st->next_id += tot;
+    st->splits += tot;
 }
 
 __global__ void k_products_finish(DevState* st, int64_t cap_e, int64_t cap_i) {
@@ -1052,6 +1198,14 @@ __global__ void k_products_finish(DevState* st, int64_t cap_e, int64_t cap_i) {
     st->n_slots[PIC_ION] += n;
     st->n_slots[PIC_ELECTRON] += n;
     st->next_id += 2ull * n;
+}
+
+// Number of bitmap words in use for the split-off ranks ((next_id + 31) / 32,
+// 0 without split-offs).
+__global__ void k_words_split(const DevState* st, uint32_t* words, int64_t maxw) {
+    unsigned long long w = (st->next_id + 31ull) >> 5;
+    if (st->n_split[0] + st->n_split[1] + st->n_split[2] == 0) w = 0;
+    *words = (uint32_t)(w < (unsigned long long)maxw ? w : (unsigned long long)maxw);
 }
 
 // Number of bitmap words in use, (next_id + 31) / 32, for the device-sized scan.
@@ -1088,6 +1242,7 @@ struct SortArgs {
     const uint32_t* total;  // number of sorted particles
     T* tmp;                 // 6 * cap
     uint32_t* tmp_id;
+    uint32_t* tmp_w;        // weighted runs
     DevState* st;
 };
 
@@ -1109,6 +1264,7 @@ __global__ void k_sort_gather(SortArgs<T> a) {
         a.tmp[4 * cap + d] = a.s.vy[i];
         a.tmp[5 * cap + d] = a.s.vz[i];
         a.tmp_id[d] = a.s.id[i];
+        if (a.s.w) a.tmp_w[d] = a.s.w[i];
     }
     // particles appended after the bins were built
     int64_t p0 = (int64_t)a.st->n_push[a.sp], p1 = (int64_t)a.st->n_slots[a.sp];
@@ -1122,6 +1278,7 @@ __global__ void k_sort_gather(SortArgs<T> a) {
         a.tmp[4 * cap + d] = a.s.vy[i];
         a.tmp[5 * cap + d] = a.s.vz[i];
         a.tmp_id[d] = a.s.id[i];
+        if (a.s.w) a.tmp_w[d] = a.s.w[i];
     }
 }
 
@@ -1138,6 +1295,7 @@ __global__ void k_sort_copyback(SortArgs<T> a) {
         a.s.vy[i] = a.tmp[4 * cap + i];
         a.s.vz[i] = a.tmp[5 * cap + i];
         a.s.id[i] = a.tmp_id[i];
+        if (a.s.w) a.s.w[i] = a.tmp_w[i];
     }
 }
 
@@ -1158,6 +1316,7 @@ __global__ void k_step_reset(DevState* st) {
     for (int s = 0; s < 3; ++s) {
         st->smax_bits[s] = 0;
         st->n_push[s] = st->n_slots[s];
+        st->n_split[s] = 0;
     }
 }
 
@@ -1175,6 +1334,7 @@ static Species<T> species(pic_ctx* c, int s) {
     r.vz = (T*)c->buf.vz[s];
     r.id = c->buf.id[s];
     r.cap = c->buf.cap[s];
+    r.w = c->cfg.weighted ? c->buf.w[s] : nullptr;
     return r;
 }
 
@@ -1243,6 +1403,7 @@ static hipError_t particles_t(pic_ctx* c, bool move) {
         a.fi_list = c->fi_list;
         a.part = c->push_part;
         a.dpart = c->push_dpart;
+        a.fi_cnt = c->fi_cnt;
         a.field0 = (move && c->circuit && s != PIC_NEUTRAL) ? (const typename V4<T>::type*)c->buf.field0 : nullptr;
         a.fi_thr = c->fi_thr;
         a.ebsi = c->ebsi;
@@ -1325,6 +1486,15 @@ static hipError_t collide_t(pic_ctx* c, bool record) {
     a.ev_cap = c->ev_cap;
     a.record = record ? 1 : 0;
     a.write_sorted = resort ? 1 : 0;
+    a.weighted = cf.weighted ? 1 : 0;
+    a.prod_c = c->prod_c;
+    a.fi_cnt = c->fi_cnt;
+    for (int s = 0; s < 3; ++s) {
+        a.split_list[s] = c->split_list[s];
+        a.split_c[s] = c->split_c[s];
+        a.split_v[s] = c->split_v[s];
+        a.split_bm[s] = c->split_bm[s];
+    }
     int tm = tic(c, PIC_T_MCC);
     // the scan and the compaction take the same grid (a wavefront of the
     // second copies the segment of the same wavefront of the first)
@@ -1360,10 +1530,34 @@ static hipError_t collide_t(pic_ctx* c, bool record) {
     p.prefix[1] = c->bm_prefix[1];
     p.ev = c->ev;
     p.ev_cap = c->ev_cap;
+    p.prod_c = cf.weighted ? c->prod_c : nullptr;
     unsigned Gp = grid_for(c->buf.cap[2]);
     hipLaunchKernelGGL(k_products<T>, dim3(Gp), dim3(kBlock), 0, c->stream, p);
     hipLaunchKernelGGL(k_products_clear<T>, dim3(Gp), dim3(kBlock), 0, c->stream, p);
     hipLaunchKernelGGL(k_products_finish, dim3(1), dim3(1), 0, c->stream, c->st, c->buf.cap[0], c->buf.cap[1]);
+    if (cf.weighted) {
+        // split-offs of partial collisions, after the products
+        uint32_t* wsplit = c->dyn + 2;
+        hipLaunchKernelGGL(k_words_split, dim3(1), dim3(1), 0, c->stream, c->st, wsplit, c->bm_words);
+        SplitArgs<T> sa;
+        for (int s = 0; s < 3; ++s) {
+            e = scan_u32(c, c->split_bm[s], c->split_pf[s], c->bm_words, wsplit, nullptr, false, true);
+            if (e != hipSuccess) return e;
+            sa.sp[s] = species<T>(c, s);
+            sa.list[s] = c->split_list[s];
+            sa.c[s] = c->split_c[s];
+            sa.v[s] = c->split_v[s];
+            sa.bm[s] = c->split_bm[s];
+            sa.pf[s] = c->split_pf[s];
+        }
+        sa.st = c->st;
+        for (int s = 0; s < 3; ++s)
+            hipLaunchKernelGGL(k_splits<T>, dim3(grid_for(c->buf.cap[s])), dim3(kBlock), 0, c->stream, sa, s);
+        for (int s = 0; s < 3; ++s)
+            hipLaunchKernelGGL(k_splits_clear<T>, dim3(grid_for(c->buf.cap[s])), dim3(kBlock), 0, c->stream, sa, s);
+        hipLaunchKernelGGL(k_splits_finish, dim3(1), dim3(1), 0, c->stream, c->st, c->buf.cap[0], c->buf.cap[1],
+                           c->buf.cap[2]);
+    }
     if (resort) {
         uint32_t* flag = c->rank_flag;
         int64_t capsum = c->buf.cap[0] + c->buf.cap[1] + c->buf.cap[2];
@@ -1382,6 +1576,7 @@ static hipError_t collide_t(pic_ctx* c, bool record) {
             sa.total = c->dyn + 1;
             sa.tmp = (T*)c->tmp;
             sa.tmp_id = (uint32_t*)((T*)c->tmp + 6 * c->tmp_cap);
+            sa.tmp_w = sa.tmp_id + c->tmp_cap;
             sa.st = c->st;
             hipLaunchKernelGGL(k_sort_gather<T>, dim3(grid_for(capsum)), dim3(kBlock), 0, c->stream, sa);
             hipLaunchKernelGGL(k_sort_copyback<T>, dim3(grid_for(sa.s.cap)), dim3(kBlock), 0, c->stream, sa);
@@ -1425,7 +1620,23 @@ struct InjArgs {
     int kind;          // 0 field emission (electrons), 1 evaporation (neutrals)
     double evap_flux;  // evaporation flux [1/(m^2 s)]
     double vsig;       // evaporation: sqrt(k_B T / m) in grid units per step
+    // superparticle weights of evaporated neutrals (Sec. 2.3.2), weighted runs
+    int weighted, w_max;
+    double n_max;
+    const uint32_t* off;  // cell offsets of the last binning (tile-major keys)
+    uint2* wk;            // per patch: {weight, atoms}
 };
+
+// Weight of the superparticles injected at a surface location (Sec. 2.3.2):
+// min(ceil(max(1, sqrt((n_cell / n_max) N_inj))), w_max), w_min = 1, n_cell the
+// superparticle density of the cell of the field point at the last binning.
+__device__ inline uint32_t inject_weight(const InjArgs& a, int64_t atoms, uint32_t cell_sp) {
+    if (a.w_max <= 1 || atoms <= 1) return 1u;
+    const double n_cell = (double)cell_sp / (a.h * a.h * a.h);
+    const double r = sqrt(n_cell / a.n_max * (double)atoms);
+    const double w = ceil(r > 1.0 ? r : 1.0);
+    return w < (double)a.w_max ? (uint32_t)w : (uint32_t)a.w_max;
+}
 
 __device__ inline double interp_phi(const Grid& g, const double* phi, double X, double Y, double Z) {
     int i = clampi((int)floor(X), 0, g.nx - 2), j = clampi((int)floor(Y), 0, g.ny - 2),
@@ -1480,7 +1691,16 @@ __device__ inline int64_t patch_count(const InjArgs& a, int64_t p, double* nexp,
         *nexp = N;
         Draw2 u = draw2(a.seed, (uint32_t)p, a.step, kTagEvap, 0);
         double fl = floor(N);
-        return (int64_t)fl + ((u.a < N - fl) ? 1 : 0);
+        const int64_t atoms = (int64_t)fl + ((u.a < N - fl) ? 1 : 0);
+        if (!a.weighted) return atoms;
+        // atoms -> superparticles of the rule's weight (the last takes the rest)
+        const int ci = clampi((int)floor(q[0] + q[3]), 0, a.g.nx - 2);
+        const int cj = clampi((int)floor(q[1] + q[4]), 0, a.g.ny - 2);
+        const int ck = clampi((int)floor(q[2] + q[5]), 0, a.g.nz - 2);
+        const uint32_t key = cell_key(a.g, ci, cj, ck);
+        const uint32_t wp = inject_weight(a, atoms, a.off[key + 1] - a.off[key]);
+        a.wk[p] = make_uint2(wp, (uint32_t)min(atoms, (int64_t)0xffffffffLL));
+        return (atoms + wp - 1) / wp;
     }
     double F = interp_phi(a.g, a.phi, q[0] + q[3], q[1] + q[4], q[2] + q[5]) / a.h;
     double J = 0.0;
@@ -1568,6 +1788,7 @@ __global__ __launch_bounds__(kInjBlock) void k_inject(InjArgs a, Species<T> e) {
     const int64_t base = (int64_t)a.st->n_slots[sp];
     const uint32_t id0 = (uint32_t)a.st->next_id;
     int64_t carry = 0;
+    unsigned long long atoms = 0;   // the weights this thread wrote
     bool over = false;
     for (int64_t c0 = 0; c0 < a.npatch; c0 += kInjChunk) {
         bool big = false;
@@ -1638,6 +1859,18 @@ __global__ __launch_bounds__(kInjBlock) void k_inject(InjArgs a, Species<T> e) {
                 e.y[m] = (T)(pt[1] + 1e-3 * pt[4]);
                 e.z[m] = (T)(pt[2] + 1e-3 * pt[5]);
                 e.id[m] = id0 + (uint32_t)(carry + q);
+                if (e.w) {
+                    uint32_t wgt = 1u;
+                    if (a.kind == 1) {
+                        const uint2 wk = a.wk[p];
+                        const int64_t k = ((int64_t)wk.y + wk.x - 1) / wk.x;
+                        wgt = j + 1 < k ? wk.x : (uint32_t)((int64_t)wk.y - (k - 1) * (int64_t)wk.x);
+                    }
+                    e.w[m] = wgt;
+                    atoms += wgt;
+                } else {
+                    atoms += 1;
+                }
             }
         }
         carry += tchunk;
@@ -1652,6 +1885,8 @@ __global__ __launch_bounds__(kInjBlock) void k_inject(InjArgs a, Species<T> e) {
     }
     const double NE = block_sum(ne, shd);
     const double CL = block_sum(cl, shd);
+    __shared__ unsigned long long shu[kInjBlock / 64];
+    const unsigned long long AT = block_sum(atoms, shu);
     if (t == 0) {
         if (a.kind == 0) {
             a.st->fn_expected += NE;
@@ -1664,8 +1899,12 @@ __global__ __launch_bounds__(kInjBlock) void k_inject(InjArgs a, Species<T> e) {
         } else {
             a.st->n_slots[sp] += (unsigned long long)carry;
             a.st->next_id += (unsigned long long)carry;
-            if (a.kind == 0) a.st->injected += (unsigned long long)carry;
-            else a.st->evaporated += (unsigned long long)carry;
+            if (a.kind == 0) {
+                a.st->injected += (unsigned long long)carry;
+            } else {
+                a.st->evaporated += (unsigned long long)carry;
+                a.st->evap_atoms += AT;
+            }
         }
     }
 }
@@ -1698,6 +1937,11 @@ hipError_t inject_phase_in(pic_ctx* c, uint32_t* cnt, double* part) {
     a.kind = 0;
     a.evap_flux = 0.0;
     a.vsig = 0.0;
+    a.weighted = c->cfg.weighted;
+    a.w_max = c->cfg.w_max;
+    a.n_max = c->cfg.n_max;
+    a.off = c->off;
+    a.wk = (uint2*)(part + 2 * ((c->npatch + kInjCountBlock - 1) / kInjCountBlock));
     if (c->npatch == 0) return hipSuccess;
     const int64_t nb = (c->npatch + kInjCountBlock - 1) / kInjCountBlock;
     // field emission, then (same work memory, in stream order) evaporation
@@ -1724,7 +1968,7 @@ hipError_t inject_phase_in(pic_ctx* c, uint32_t* cnt, double* part) {
 
 template <typename T>
 __global__ void k_load(Species<T> s, int sp, const T* x, const T* y, const T* z, const T* vx, const T* vy,
-                       const T* vz, int64_t n, DevState* st) {
+                       const T* vz, const uint32_t* w, int64_t n, DevState* st) {
     int64_t base = (int64_t)st->n_slots[sp];
     if (base + n > s.cap) return;
     uint32_t id0 = (uint32_t)st->next_id;
@@ -1738,6 +1982,7 @@ __global__ void k_load(Species<T> s, int sp, const T* x, const T* y, const T* z,
         s.vy[m] = vy[i];
         s.vz[m] = vz[i];
         s.id[m] = id0 + (uint32_t)i;
+        if (s.w) s.w[m] = w ? w[i] : 1u;
     }
 }
 
@@ -1756,11 +2001,12 @@ hipError_t load_particles(pic_ctx* c, const pic_particles* src) {
     if (c->cfg.precision == PIC_F32) {
         hipLaunchKernelGGL(k_load<float>, dim3(grid_for(src->n)), dim3(kBlock), 0, c->stream, species<float>(c, s), s,
                            (const float*)src->x, (const float*)src->y, (const float*)src->z, (const float*)src->vx,
-                           (const float*)src->vy, (const float*)src->vz, src->n, c->st);
+                           (const float*)src->vy, (const float*)src->vz, src->w, src->n, c->st);
     } else {
         hipLaunchKernelGGL(k_load<double>, dim3(grid_for(src->n)), dim3(kBlock), 0, c->stream, species<double>(c, s),
                            s, (const double*)src->x, (const double*)src->y, (const double*)src->z,
-                           (const double*)src->vx, (const double*)src->vy, (const double*)src->vz, src->n, c->st);
+                           (const double*)src->vx, (const double*)src->vy, (const double*)src->vz, src->w, src->n,
+                           c->st);
     }
     hipLaunchKernelGGL(k_load_finish, dim3(1), dim3(1), 0, c->stream, c->st, s, src->n, c->buf.cap[s]);
     return hipGetLastError();
@@ -1770,7 +2016,9 @@ hipError_t load_particles(pic_ctx* c, const pic_particles* src) {
 // Moments: per species the alive count and kinetic energy, and the
 // Shockley-Ramo current I = sum q v . E0(x) (Sec. 2.3.1) with E0 the field of
 // the unit-anode Laplace problem. Fixed grid and fixed-order reductions.
-// out (device, per block): 7 doubles {n_e, n_i, n_n, ke_e, ke_i, ke_n, i_sr}.
+// out (device, per block): 10 doubles {n_e, n_i, n_n, ke_e, ke_i, ke_n, i_sr,
+// and the physical counts (sums of the weights) of the three species}.
+constexpr int kMomVals = 10;
 
 constexpr int kMomBlocks = 512;
 
@@ -1780,7 +2028,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(Species<T> s0, Species<T> s1
                                                      const DevState* st, double* part, const int64_t* rho,
                                                      long long* qpart) {
     __shared__ double sh[kBlock / 64];
-    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    double acc[kMomVals] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const Species<T>* S[3] = {&s0, &s1, &s2};
     const double mass[3] = {kMe, m_ion, m_ion};
     const double q[3] = {-kQe, kQe, 0.0};
@@ -1791,18 +2039,20 @@ __global__ __launch_bounds__(kBlock) void k_moments(Species<T> s0, Species<T> s1
         for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
             if (P.id[i] == kDead) continue;
             double vx = (double)P.vx[i] * sv, vy = (double)P.vy[i] * sv, vz = (double)P.vz[i] * sv;
+            const double wp = P.w ? (double)P.w[i] : 1.0;
             acc[s] += 1.0;
-            acc[3 + s] += 0.5 * mass[s] * (vx * vx + vy * vy + vz * vz);
+            acc[7 + s] += wp;
+            acc[3 + s] += wp * 0.5 * mass[s] * (vx * vx + vy * vy + vz * vz);
             if (s != 2) {
                 T ex, ey, ez;
                 gather<T>(g, E0, P.x[i], P.y[i], P.z[i], ex, ey, ez);
-                acc[6] += q[s] * (vx * (double)ex + vy * (double)ey + vz * (double)ez);
+                acc[6] += wp * q[s] * (vx * (double)ex + vy * (double)ey + vz * (double)ez);
             }
         }
     }
-    for (int k = 0; k < 7; ++k) {
+    for (int k = 0; k < kMomVals; ++k) {
         double t = block_sum(acc[k], sh);
-        if (threadIdx.x == 0) part[blockIdx.x * 7 + k] = t;
+        if (threadIdx.x == 0) part[blockIdx.x * kMomVals + k] = t;
     }
     long long qs = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < g.nn; i += stride) qs += rho[i];
@@ -1811,13 +2061,14 @@ __global__ __launch_bounds__(kBlock) void k_moments(Species<T> s0, Species<T> s1
     if (threadIdx.x == 0) qpart[blockIdx.x] = tq;
 }
 
+// out: the 7 sums, the total charge (int64 in out[7]), the 3 physical counts
 __global__ void k_moments_final(const double* part, int nb, const long long* qpart, double* out) {
     __shared__ double sh[kBlock / 64];
-    for (int k = 0; k < 7; ++k) {
+    for (int k = 0; k < kMomVals; ++k) {
         double s = 0.0;
-        for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[b * 7 + k];
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) s += part[b * kMomVals + k];
         double t = block_sum(s, sh);
-        if (threadIdx.x == 0) out[k] = t;
+        if (threadIdx.x == 0) out[k < 7 ? k : k + 1] = t;
     }
     __shared__ long long shl[kBlock / 64];
     long long q = 0;
@@ -1832,13 +2083,13 @@ hipError_t moments_phase(pic_ctx* c, double* out_dev) {
     if (c->cfg.precision == PIC_F32)
         hipLaunchKernelGGL(k_moments<float>, dim3(kMomBlocks), dim3(kBlock), 0, c->stream, species<float>(c, 0),
                            species<float>(c, 1), species<float>(c, 2), (const float4*)c->buf.field0, c->g, sv,
-                           c->cfg.m_ion, c->st, part, c->buf.rho, (long long*)(part + 7 * kMomBlocks));
+                           c->cfg.m_ion, c->st, part, c->buf.rho, (long long*)(part + kMomVals * kMomBlocks));
     else
         hipLaunchKernelGGL(k_moments<double>, dim3(kMomBlocks), dim3(kBlock), 0, c->stream, species<double>(c, 0),
                            species<double>(c, 1), species<double>(c, 2), (const double4*)c->buf.field0, c->g, sv,
-                           c->cfg.m_ion, c->st, part, c->buf.rho, (long long*)(part + 7 * kMomBlocks));
+                           c->cfg.m_ion, c->st, part, c->buf.rho, (long long*)(part + kMomVals * kMomBlocks));
     hipLaunchKernelGGL(k_moments_final, dim3(1), dim3(kBlock), 0, c->stream, part, kMomBlocks,
-                       (const long long*)(part + 7 * kMomBlocks), out_dev);
+                       (const long long*)(part + kMomVals * kMomBlocks), out_dev);
     return hipGetLastError();
 }
 

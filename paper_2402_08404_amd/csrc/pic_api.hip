@@ -90,6 +90,8 @@ const char* check_config(const pic_config* cfg) {
     if (cfg->circuit_R > 0.0 && !(cfg->circuit_C > 0.0 && std::isfinite(cfg->circuit_C)))
         return "the circuit needs circuit_C > 0";
     if (cfg->surface_T > 0.0 && cfg->fn_rings == 0) return "evaporation needs the surface patches (fn_rings, fn_az)";
+    if (cfg->weighted != 0 && cfg->weighted != 1) return "weighted must be 0 or 1";
+    if (cfg->weighted && cfg->w_max > 1 && !(cfg->n_max > 0.0)) return "the injection weight rule needs n_max > 0";
     return nullptr;
 }
 
@@ -158,7 +160,9 @@ size_t pic::scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[
     t->push_dpart = (double*)take(8192 * 4 * 8);
     const int64_t npatch = fn_patches(cfg);
     t->inj_cnt = (uint32_t*)take(std::max<int64_t>(npatch, 1) * 4);
-    t->inj_part = (double*)take(2 * std::max<int64_t>((npatch + kInjCountBlock - 1) / kInjCountBlock, 1) * 8);
+    // per count block two doubles, then a {weight, atoms} pair per patch
+    t->inj_part = (double*)take(2 * std::max<int64_t>((npatch + kInjCountBlock - 1) / kInjCountBlock, 1) * 8 +
+                                std::max<int64_t>(npatch, 1) * 8);
     t->nflag = (uint32_t*)take(cap[2] * 4);
     t->prod_list = (uint32_t*)take(cap[2] * 4);
     t->prod_ev = (int32_t*)take(cap[2] * 4);
@@ -171,7 +175,7 @@ size_t pic::scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[
     t->scan_blocks = (uint32_t*)take(scan_blocks * 4);
     t->rank_flag = (uint32_t*)take(capsum * 4);
     t->rank = (uint32_t*)take(capsum * 4);
-    t->tmp = take(capmax * (6 * tsz + 4));
+    t->tmp = take(capmax * (6 * tsz + 8));  // six state arrays, ids, weights
     t->cg_r = (double*)take(nn * 8);
     t->cg_p0 = (double*)take(nn * 8);
     t->cg_p1 = (double*)take(nn * 8);
@@ -179,6 +183,17 @@ size_t pic::scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[
     t->phi_prev = (double*)take(nn * 8);
     t->partials = (double*)take(parts * 8);
     t->mg = take(mg_bytes(cfg));
+    if (cfg->weighted) {
+        t->fi_cnt = (uint32_t*)take(cap[2] * 4);
+        t->prod_c = (uint32_t*)take(cap[2] * 4);
+        for (int s = 0; s < 3; ++s) {
+            t->split_list[s] = (uint32_t*)take(cap[s] * 4);
+            t->split_c[s] = (uint32_t*)take(cap[s] * 4);
+            t->split_v[s] = (double*)take(cap[s] * 24);
+            t->split_bm[s] = (uint32_t*)take(words * 4);
+            t->split_pf[s] = (uint32_t*)take(words * 4);
+        }
+    }
     if (c) {
         c->scan_blocks_n = scan_blocks;
         c->partials_n = parts;
@@ -223,6 +238,12 @@ pic_status pic_init(const pic_config* cfg, const pic_buffers* bufs, void* hip_st
     if (!bufs->phi || !bufs->phi1 || !bufs->rho || !bufs->field || !bufs->field0 || !bufs->node_type || !bufs->scratch)
         return PIC_E_INVALID_ARG;
     if (((uintptr_t)bufs->scratch) % 256 != 0) return PIC_E_INVALID_ARG;
+    if (cfg->weighted)
+        for (int s = 0; s < 3; ++s)
+            if (bufs->cap[s] > 0 && !bufs->w[s]) {
+                g_init_error = "a weighted run needs the weight arrays";
+                return PIC_E_INVALID_ARG;
+            }
     size_t need = scratch_layout(nullptr, cfg, bufs->cap, nullptr);
     if (bufs->scratch_bytes < need) {
         g_init_error = "scratch too small";
@@ -322,6 +343,9 @@ pic_status pic_init(const pic_config* cfg, const pic_buffers* bufs, void* hip_st
     H(launch_zero(c->dyn, 64 * 4, c->stream), "zero");
     H(launch_zero(c->nflag, bufs->cap[2] * 4, c->stream), "zero");
     for (int k = 0; k < 2; ++k) H(launch_zero(c->bitmap[k], c->bm_words * 4, c->stream), "zero");
+    H(launch_zero(c->off, ((size_t)g.nkeys + 1) * 4, c->stream), "zero");
+    if (cfg->weighted)
+        for (int k = 0; k < 3; ++k) H(launch_zero(c->split_bm[k], c->bm_words * 4, c->stream), "zero");
     H(launch_zero(bufs->rho, g.nn * 8, c->stream), "zero");
     H(static_work_setup(&c->static_work), "static work array");
     H(launch_node_types(c), "node types");
@@ -590,7 +614,7 @@ pic_status pic_moments(pic_ctx* c, pic_moments_t* out) {
     if (c->failed) return PIC_E_STATE;
     pic_status s = hip_check(c, moments_phase(c, c->mom_out), "moments");
     if (s != PIC_OK) return s;
-    double host[8];
+    double host[11];
     s = hip_check(c, hipMemcpyAsync(host, c->mom_out, sizeof(host), hipMemcpyDeviceToHost, c->stream), "copy");
     if (s != PIC_OK) return s;
     s = sync_state(c);
@@ -626,6 +650,10 @@ pic_status pic_moments(pic_ctx* c, pic_moments_t* out) {
     out->v_gap = h->v_gap;
     out->i_gap = h->i_gap;
     out->i_tot = h->i_tot;
+    for (int k = 0; k < 3; ++k) out->n_phys[k] = (int64_t)llround(host[8 + k]);
+    for (int k = 0; k < 5; ++k) out->events_w[k] = (int64_t)h->events_w[k];
+    out->splits = (int64_t)h->splits;
+    out->evap_atoms = (int64_t)h->evap_atoms;
     return s;
 }
 

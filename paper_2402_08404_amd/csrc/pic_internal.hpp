@@ -30,6 +30,9 @@ constexpr int kBlock = 256;
 
 // Third Philox counter word: purpose of the draw.
 constexpr uint32_t kTagMcc1 = 1, kTagMcc2 = 2, kTagPair1 = 3, kTagPair2 = 4, kTagFi = 5, kTagInj = 6, kTagEvap = 7;
+// added to a tag for the draws of the second and later sub-particles of a
+// weighted superparticle (sub-particle q >= 1 draws with counter word q)
+constexpr uint32_t kTagSub = 16;
 
 // Device-resident counters and scalars of one context.
 struct DevState {
@@ -63,6 +66,11 @@ struct DevState {
     double bomb_e[2];                  // kinetic energy of ions absorbed at the cathode plane / the tip [J]
     double isr[2];                     // Shockley-Ramo current of the last push, electrons and ions [A]
     double v_gap, i_gap, i_tot;        // RC circuit: gap voltage (anode potential), currents [V, A]
+    // superparticle weights
+    unsigned long long events_w[5];    // physical collisions per kind (sum of N_coll)
+    unsigned long long n_split[3];     // superparticles split off in this collide phase, per species
+    unsigned long long splits;         // cumulative split-offs
+    unsigned long long evap_atoms;     // cumulative evaporated atoms
 };
 
 // Cells are numbered tile-major: tiles of kTile^3 cells, tile index
@@ -99,6 +107,7 @@ struct Species {
     T *x, *y, *z, *vx, *vy, *vz;
     uint32_t* id;
     int64_t cap;
+    uint32_t* w;   // superparticle weights (null: every weight is 1)
 };
 
 template <typename T>
@@ -427,6 +436,14 @@ struct pic_ctx {
     int learn_fallback = 1;          // judge the learned guess against V0 phi1 before each solve
     void* static_work = nullptr;     // this device's copy of the static work array (pic_inject_noalloc)
     double* push_dpart = nullptr;    // per-block FP64 partials of the push kernels (8192 x 4)
+    // superparticle weights (cfg.weighted only)
+    uint32_t* fi_cnt = nullptr;      // cap neutral: field-ionized units of a candidate neutral
+    uint32_t* prod_c = nullptr;      // cap neutral: ionized units of a neutral with a product
+    uint32_t* split_list[3] = {};    // per species: parent slots of the split-offs of the phase
+    uint32_t* split_c[3] = {};       // per species and slot: units split off
+    double* split_v[3] = {};         // per species and slot: velocity of the split-off (3 values)
+    uint32_t* split_bm[3] = {};      // per species: split-off parents as a bitmap over ids
+    uint32_t* split_pf[3] = {};      // their word prefix counts
     bool circuit = false;            // cfg.circuit_R > 0: the anode follows the RC circuit
     double evap_flux = 0.0;          // Clausius-Clapeyron flux at cfg.surface_T [1/(m^2 s)]
     double evap_vsig = 0.0;          // sqrt(k_B T / m) dt / h
@@ -481,10 +498,11 @@ hipError_t cell_bins(pic_ctx* c);
 hipError_t inject_phase(pic_ctx* c);
 // the emission with its per-patch counts and per-block sums in cnt and part
 hipError_t inject_phase_in(pic_ctx* c, uint32_t* cnt, double* part);
-// bytes of work memory of the emission (counts and block sums)
+// bytes of work memory of the surface injection (counts, block sums and, for
+// the weights of evaporated neutrals, a {weight, atoms} pair per patch)
 inline size_t inject_work_bytes(int64_t npatch) {
     const int64_t nb = (npatch + kInjCountBlock - 1) / kInjCountBlock;
-    return (((size_t)npatch * 4 + 255) & ~(size_t)255) + (size_t)nb * 16;
+    return (((size_t)npatch * 4 + 255) & ~(size_t)255) + (size_t)nb * 16 + (size_t)npatch * 8;
 }
 hipError_t load_particles(pic_ctx* c, const pic_particles* src);
 hipError_t moments_phase(pic_ctx* c, double* out_dev);

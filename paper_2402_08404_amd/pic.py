@@ -48,19 +48,20 @@ class pic_config(C.Structure):
                 ("fn_rings", C.c_int32), ("fn_az", C.c_int32), ("laplace_rtol", C.c_double),
                 ("step_rtol", C.c_double), ("step_maxit", C.c_int32), ("sort_every", C.c_int32),
                 ("id_capacity", C.c_int64), ("stencil_blocks", C.c_int32), ("step_guess", C.c_int32),
-                ("surface_T", C.c_double), ("circuit_R", C.c_double), ("circuit_C", C.c_double)]
+                ("surface_T", C.c_double), ("circuit_R", C.c_double), ("circuit_C", C.c_double),
+                ("weighted", C.c_int32), ("w_max", C.c_int32), ("n_max", C.c_double)]
 
 
 class pic_buffers(C.Structure):
     _fields_ = [(k, C.c_void_p * 3) for k in ("x", "y", "z", "vx", "vy", "vz")] + \
                [("id", C.c_void_p * 3), ("cap", C.c_int64 * 3), ("phi", C.c_void_p), ("phi1", C.c_void_p),
                 ("rho", C.c_void_p), ("field", C.c_void_p), ("field0", C.c_void_p), ("node_type", C.c_void_p),
-                ("scratch", C.c_void_p), ("scratch_bytes", C.c_size_t)]
+                ("scratch", C.c_void_p), ("scratch_bytes", C.c_size_t), ("w", C.c_void_p * 3)]
 
 
 class pic_particles(C.Structure):
     _fields_ = [("species", C.c_int32), ("pad", C.c_int32), ("n", C.c_int64)] + \
-               [(k, C.c_void_p) for k in ("x", "y", "z", "vx", "vy", "vz")]
+               [(k, C.c_void_p) for k in ("x", "y", "z", "vx", "vy", "vz")] + [("w", C.c_void_p)]
 
 
 class pic_solve_info(C.Structure):
@@ -76,7 +77,9 @@ class pic_moments_t(C.Structure):
                 ("apex_field1", C.c_double), ("error", C.c_int32), ("last_cg_iters", C.c_int32),
                 ("last_cg_relres", C.c_double), ("cg_iters_total", C.c_int64),
                 ("evaporated", C.c_int64), ("evap_expected", C.c_double), ("bomb_energy", C.c_double * 2),
-                ("v_gap", C.c_double), ("i_gap", C.c_double), ("i_tot", C.c_double)]
+                ("v_gap", C.c_double), ("i_gap", C.c_double), ("i_tot", C.c_double),
+                ("n_phys", C.c_int64 * 3), ("events_w", C.c_int64 * 5), ("splits", C.c_int64),
+                ("evap_atoms", C.c_int64)]
 
 
 class pic_unet_config(C.Structure):
@@ -197,7 +200,8 @@ def pic_moments(ctx) -> dict:
             "fn_expected": m.fn_expected, "v0": m.v0, "apex_field1": m.apex_field1, "error": m.error,
             "last_cg_iters": m.last_cg_iters, "last_cg_relres": m.last_cg_relres, "cg_iters_total": m.cg_iters_total,
             "evaporated": m.evaporated, "evap_expected": m.evap_expected, "bomb_energy": np.array(m.bomb_energy[:]),
-            "v_gap": m.v_gap, "i_gap": m.i_gap, "i_tot": m.i_tot}
+            "v_gap": m.v_gap, "i_gap": m.i_gap, "i_tot": m.i_tot, "n_phys": np.array(m.n_phys[:]),
+            "events_w": np.array(m.events_w[:]), "splits": m.splits, "evap_atoms": m.evap_atoms}
 
 
 def pic_events(ctx, cap: int) -> list:
@@ -292,7 +296,8 @@ def pic_training_sample(ctx, x: int, y: int) -> float:
 
 
 def make_config(cfg: workloads.Config, precision=PIC_F64, solver=PIC_SOLVER_CG, laplace_rtol=1e-13,
-                step_rtol=1e-8, step_maxit=20000, sort_every=16, id_capacity=0, stencil_blocks=0, step_guess=0):
+                step_rtol=1e-8, step_maxit=20000, sort_every=16, id_capacity=0, stencil_blocks=0, step_guess=0,
+                weighted=False):
     keep = [np.ascontiguousarray(t, dtype=np.float64) for t in (cfg.xs_el, cfg.xs_iz, cfg.xs_cx)]
     dp = C.POINTER(C.c_double)
     c = pic_config(nx=cfg.nx, ny=cfg.ny, nz=cfg.nz, precision=precision, h=cfg.h, tip_r=cfg.tip_r,
@@ -303,7 +308,8 @@ def make_config(cfg: workloads.Config, precision=PIC_F64, solver=PIC_SOLVER_CG, 
                    laplace_rtol=laplace_rtol, step_rtol=step_rtol, step_maxit=step_maxit, sort_every=sort_every,
                    id_capacity=id_capacity, stencil_blocks=stencil_blocks, step_guess=step_guess,
                    surface_T=getattr(cfg, "surface_T", 0.0), circuit_R=getattr(cfg, "circuit_R", 0.0),
-                   circuit_C=getattr(cfg, "circuit_C", 0.0))
+                   circuit_C=getattr(cfg, "circuit_C", 0.0), weighted=1 if weighted else 0,
+                   w_max=int(getattr(cfg, "w_max", 1)), n_max=float(getattr(cfg, "n_max", 1e24)))
     return c, keep
 
 
@@ -312,8 +318,11 @@ class Simulation:
     pic_buffers, and the context."""
 
     def __init__(self, cfg: workloads.Config, caps=(1 << 16, 1 << 14, 1 << 14), precision=PIC_F64,
-                 solver=PIC_SOLVER_CG, device="cuda", stream: torch.cuda.Stream | None = None, **kw):
+                 solver=PIC_SOLVER_CG, device="cuda", stream: torch.cuda.Stream | None = None, weighted=False, **kw):
+        """weighted: every superparticle carries a weight (Sec. 2.3.2)."""
         self.cfg = cfg
+        self.weighted = bool(weighted)
+        kw["weighted"] = self.weighted
         self.device = torch.device(device)
         self.dtype = torch.float32 if precision == PIC_F32 else torch.float64
         self.precision = precision
@@ -326,6 +335,8 @@ class Simulation:
             cap = max(self.caps[s], 1)
             arrs = {k: torch.zeros(cap, dtype=self.dtype, device=dev) for k in ("x", "y", "z", "vx", "vy", "vz")}
             arrs["id"] = torch.full((cap,), -1, dtype=torch.int32, device=dev)
+            if self.weighted:
+                arrs["w"] = torch.ones(cap, dtype=torch.int32, device=dev)
             self.sp.append(arrs)
         self.phi = torch.zeros(nn, dtype=torch.float64, device=dev)
         self.phi1 = torch.zeros(nn, dtype=torch.float64, device=dev)
@@ -343,6 +354,8 @@ class Simulation:
                 getattr(b, k)[s] = self.sp[s][k].data_ptr()
             b.id[s] = self.sp[s]["id"].data_ptr()
             b.cap[s] = self.caps[s]
+            if self.weighted:
+                b.w[s] = self.sp[s]["w"].data_ptr()
         b.phi, b.phi1, b.rho = self.phi.data_ptr(), self.phi1.data_ptr(), self.rho.data_ptr()
         b.field, b.field0, b.node_type = self.field.data_ptr(), self.field0.data_ptr(), self.node_type.data_ptr()
         b.scratch = base + self._scratch_off
@@ -377,6 +390,10 @@ class Simulation:
             t = {k: torch.as_tensor(np.asarray(a[k]), dtype=self.dtype).to(self.device) for k in
                  ("x", "y", "z", "vx", "vy", "vz")}
             src = pic_particles(species=s, n=n, **{k: v.data_ptr() for k, v in t.items()})
+            if self.weighted and "w" in a:
+                tw = torch.as_tensor(np.asarray(a["w"], np.int64).astype(np.int32)).to(self.device)
+                t["w"] = tw
+                src.w = tw.data_ptr()
             torch.cuda.synchronize(self.device)
             pic_inject(self.ctx, src)
 
@@ -413,6 +430,8 @@ class Simulation:
             alive = ids != DEAD
             d = {k: v[alive] for k, v in d.items()}
             d["id"] = ids[alive]
+            d["w"] = (self.sp[s]["w"][:n].cpu().numpy().view(np.uint32)[alive] if self.weighted
+                      else np.ones(int(alive.sum()), np.uint32))
             out.append(d)
         return out
 

@@ -89,6 +89,8 @@ def compare_states(cfg, gpu_st, orc_st, pos_tol, vel_tol, margin_tol=None, kick=
             continue
         a = np.array([gi[i] for i in common])
         b = np.array([oi[i] for i in common])
+        if "w" in g and "w" in o:
+            assert np.array_equal(g["w"][a], o["w"][b]), (s, "weights")
         for k in ("x", "y", "z"):
             d = np.abs(g[k][a] - o[k][b])
             assert (d <= pos_tol * np.maximum(1.0, np.abs(o[k][b]))).all(), (s, k, d.max())
