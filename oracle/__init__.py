@@ -8,7 +8,8 @@ numpy arrays and a configuration object with the attributes of
 
 One step follows the order the paper gives for the PIC-MCC loop (Sec. 2.2 and
 Sec. 2.3.1): emission, push with boundary removal, collisions and field
-ionization, charge deposition, Poisson solve and node field.
+ionization, merging of superparticles (when enabled, Sec. 2.3.2), charge
+deposition, Poisson solve and node field.
 """
 from __future__ import annotations
 
@@ -295,6 +296,7 @@ class Oracle:
         self.cell_count = np.zeros((cfg.nx - 1) * (cfg.ny - 1) * (cfg.nz - 1), np.int64)
         self.events_w = np.zeros(5, np.int64)     # physical collisions per kind (sum of N_coll)
         self.splits = 0
+        self.merges = np.zeros(3, np.int64)      # merged pairs per species
         self.last_events = []
         self.last_fragile = set()
         self.last_solve = (0, 0.0)
@@ -479,6 +481,59 @@ class Oracle:
         self.bsi_skips += int(out.n_bsi_skip)
         return self.last_events
 
+    def merge(self, id_limit: int) -> int:
+        """Merging of superparticles (Sec. 2.3.2, Eq. of r_m and v_m): two
+        superparticles of one species become one of weight w1 + w2 whose
+        position and velocity are the weighted means (w1 a1 + w2 a2) / (w1 + w2)
+        (the paper's r1 mu / w2 + r2 mu / w1 with mu = w1 w2 / (w1 + w2)).
+        The paper leaves the choice of pairs open; here, per cell (the cell of
+        the current position) and species, the alive superparticles with ids
+        below id_limit (those that existed before this step's collisions) are
+        taken in ascending id order, and when there are N > merge_max of them
+        the first k = min(floor(N / 2), N - merge_max) consecutive pairs merge,
+        each keeping its lower id; a pair whose summed weight would exceed
+        w_max stays as it is. Returns the number of merged pairs."""
+        cfg = self.cfg
+        if cfg.merge_max <= 0:
+            return 0
+        nx1, ny1 = cfg.nx - 1, cfg.ny - 1
+        done = 0
+        for s in range(3):
+            st = self.sp[s]
+            n = st.n
+            if n < 2:
+                continue
+            ids = st.id[:n].astype(np.int64)
+            cand = np.nonzero(ids < id_limit)[0]
+            i = np.clip(np.floor(st.a["x"][cand]).astype(np.int64), 0, nx1 - 1)
+            j = np.clip(np.floor(st.a["y"][cand]).astype(np.int64), 0, ny1 - 1)
+            k = np.clip(np.floor(st.a["z"][cand]).astype(np.int64), 0, cfg.nz - 2)
+            cell = (k * ny1 + j) * nx1 + i
+            order = np.lexsort((ids[cand], cell))
+            cand, cell = cand[order], cell[order]
+            starts = np.flatnonzero(np.r_[True, cell[1:] != cell[:-1]]) if len(cand) else np.zeros(0, np.int64)
+            ends = np.r_[starts[1:], len(cand)].astype(np.int64)
+            gone = np.zeros(n, bool)
+            for a0, a1 in zip(starts, ends):
+                N = int(a1 - a0)
+                if N <= cfg.merge_max:
+                    continue
+                for q in range(min(N // 2, N - cfg.merge_max)):
+                    pa, pb = cand[a0 + 2 * q], cand[a0 + 2 * q + 1]
+                    w1, w2 = int(st.w[pa]), int(st.w[pb])
+                    if w1 + w2 > cfg.w_max:
+                        continue
+                    fa, fb = float(w1), float(w2)
+                    for key in ("x", "y", "z", "vx", "vy", "vz"):
+                        v = st.a[key]
+                        v[pa] = (fa * v[pa] + fb * v[pb]) / (fa + fb)
+                    st.w[pa] = w1 + w2
+                    gone[pb] = True
+                    self.merges[s] += 1
+                    done += 1
+            st.keep(~gone)
+        return done
+
     def step(self, rtol: float = 1e-8, inject: bool = True, collide_flags: int = COLL_ALL,
              solve: bool = True):
         if inject:
@@ -487,8 +542,11 @@ class Oracle:
         self.push()
         if self.cfg.circuit_R > 0:
             self.circuit_step(self.i_gap)
+        id_limit = self.next_id
         if collide_flags:
             self.collide(collide_flags)
+        if self.cfg.merge_every > 0 and self.step_no % self.cfg.merge_every == 0:
+            self.merge(id_limit)
         self.deposit()
         if solve:
             self.solve(rtol=rtol)
@@ -504,7 +562,7 @@ class Oracle:
                 "i_gap": self.i_gap, "i_tot": self.i_tot, "bomb_energy": self.bomb_energy.copy(),
                 "evaporated": self.evaporated, "evap_atoms": self.evap_atoms, "evap_expected": self.evap_expected,
                 "n_phys": np.array([int(st.w[: st.n].sum()) for st in self.sp], np.int64),
-                "events_w": self.events_w.copy(), "splits": self.splits}
+                "events_w": self.events_w.copy(), "splits": self.splits, "merges": self.merges.copy()}
 
     # -- helpers for tests ----------------------------------------------------
     def gather(self, E: np.ndarray, X, Y, Z) -> np.ndarray:

@@ -57,8 +57,10 @@ class Config:
     surface_T: float = 0.0   # prescribed tip surface temperature for neutral evaporation [K] (0: none)
     circuit_R: float = 0.0   # series resistance of the external RC circuit [ohm] (0: fixed anode potential)
     circuit_C: float = 0.0   # gap capacitance of the RC circuit [F]
-    w_max: int = 1           # largest superparticle weight given to evaporated neutrals (1: all weights 1)
+    w_max: int = 1           # largest superparticle weight that injection and merging create
     n_max: float = 1e24      # SP number density above which evaporated neutrals get heavier [1/m^3] (1e-6 per A^3)
+    merge_every: int = 0     # merging of superparticles every this many steps (0: never)
+    merge_max: int = 0       # superparticles of one species per cell above which pairs of them merge
 
     @property
     def n_nodes(self) -> int:

@@ -1,12 +1,16 @@
-"""Each pin of tests/test_oracle_readings.py must catch the plausible mistake
-it is there for. A copy of oracle.c with that one mistake planted is built
-on the CPU, and the pin, run against the copy, must fail; the same pin passes
-on the real oracle (tests/test_oracle_readings.py)."""
+"""Each pin of the oracle tests must catch the plausible mistake it is there
+for. A copy of oracle.c with that one mistake planted is built on the CPU (or,
+for the merging of superparticles, written in Python, a copy of
+Oracle.merge), and the pin, run against the copy, must fail; the same pin
+passes on the real oracle in its own test module."""
+import inspect
 import os
+import textwrap
 
 import pytest
 
 import oracle
+import test_oracle_merging as M
 import test_oracle_readings as R
 import test_oracle_surface as S
 import test_oracle_weights as WT
@@ -82,3 +86,30 @@ def test_pin_catches_planted_mistake(tmp_path, name, old, new, pin):
     with oracle.use_library(path):
         with pytest.raises(AssertionError):
             pin()
+
+
+# mistakes planted in the Python part of the oracle (merging of superparticles)
+PY_MUTATIONS = [
+    ("centre of mass with the weights swapped",
+     "v[pa] = (fa * v[pa] + fb * v[pb]) / (fa + fb)", "v[pa] = (fb * v[pa] + fa * v[pb]) / (fa + fb)",
+     M.pin_merge_conservation),
+    ("pairs in descending id order",
+     "order = np.lexsort((ids[cand], cell))", "order = np.lexsort((-ids[cand], cell))", M.pin_pair_choice),
+    ("merging down to floor(N / 2) regardless of merge_max",
+     "for q in range(min(N // 2, N - cfg.merge_max)):", "for q in range(N // 2):", M.pin_pair_choice),
+    ("merged weights above w_max",
+     "if w1 + w2 > cfg.w_max:", "if False:", M.pin_w_max_and_id_limit),
+    ("products of this step's collisions merged",
+     "cand = np.nonzero(ids < id_limit)[0]", "cand = np.arange(n)", M.pin_w_max_and_id_limit),
+]
+
+
+@pytest.mark.parametrize("name,old,new,pin", PY_MUTATIONS, ids=[m[0] for m in PY_MUTATIONS])
+def test_merge_pin_catches_planted_mistake(monkeypatch, name, old, new, pin):
+    src = textwrap.dedent(inspect.getsource(oracle.Oracle.merge))
+    assert src.count(old) == 1, f"mutation site not found: {name}"
+    ns = dict(vars(oracle))
+    exec(src.replace(old, new), ns)
+    monkeypatch.setattr(oracle.Oracle, "merge", ns["merge"])
+    with pytest.raises(AssertionError):
+        pin()
