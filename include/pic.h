@@ -128,8 +128,18 @@ typedef struct pic_config {
     int32_t weighted;      /* 1: every superparticle carries an integer weight (pic_buffers.w; physical
                               particles per superparticle, the smallest weight w_min being 1); collisions
                               split superparticles; 0: every weight is 1 and no weight array is read */
-    int32_t w_max;         /* largest weight given to evaporated neutrals by the injection rule (<= 1: 1) */
+    int32_t w_max;         /* largest weight that the injection rule gives evaporated neutrals and that
+                              merging creates (<= 1: injection weights 1, no merging) */
     double n_max;          /* superparticle density [1/m^3] of the injection rule (1e24 = 1e-6 per A^3) */
+    /* Merging of superparticles (Sec. 2.3.2; needs weighted = 1): in the collide phase of every step
+     * whose counter is a multiple of merge_every, per cell and species, the superparticles binned by
+     * the push that are still alive are taken in ascending id order; when there are N > merge_max of
+     * them, the first min(floor(N/2), N - merge_max) consecutive pairs merge into one superparticle of
+     * weight w1 + w2 at the weighted mean position and velocity (the centre of mass), keeping the lower
+     * id; a pair whose summed weight would exceed w_max is left alone. The node charge is corrected
+     * exactly (integer deposit), and such a step runs its collisions before the solve. */
+    int32_t merge_every;   /* 0: no merging */
+    int32_t merge_max;     /* >= 1 when merge_every > 0 */
 } pic_config;
 
 typedef struct pic_buffers {
@@ -206,6 +216,7 @@ typedef struct pic_moments_t {
     int64_t events_w[5];       /* cumulative physical collisions per event kind (sum of N_coll) */
     int64_t splits;            /* cumulative superparticles split off by partial collisions */
     int64_t evap_atoms;        /* cumulative evaporated atoms (the weights of the evaporated neutrals) */
+    int64_t merges[3];         /* cumulative merged pairs per species */
 } pic_moments_t;
 
 typedef struct pic_event {

@@ -1448,6 +1448,128 @@ hipError_t particles_phase(pic_ctx* c, bool move) {
     return c->cfg.precision == PIC_F32 ? particles_t<float>(c, move) : particles_t<double>(c, move);
 }
 
+// ---------------------------------------------------------------------------
+// Merging of superparticles (Sec. 2.3.2, the centre-of-mass merge of two
+// superparticles of one type). The paper does not say which pairs merge:
+// per cell and species, the superparticles binned by this step's push that
+// are still alive are ranked by id; with N > merge_max of them, ranks (0,1),
+// (2,3), ... up to k = min(floor(N/2), N - merge_max) pairs merge, keeping
+// the lower id, unless the summed weight would exceed w_max. One kernel picks
+// the partner of every rank-even entry (reading only), a second applies the
+// merges, so the picks never see a half-merged cell. The node charge was
+// deposited before the collisions; the merge subtracts the two deposits and
+// adds the merged one, integer sums, so the result equals a fresh deposit.
+
+template <typename T>
+struct MergeArgs {
+    Species<T> sp[3];
+    Grid g;
+    const uint32_t* off;    // cell offsets of the push's binning
+    const uint2* bins;      // {species << 30 | slot, id} in cell order
+    const uint32_t* key[3]; // cell key of every slot from the push
+    uint32_t* pick;         // per bin entry: the partner's entry, or kDead
+    int64_t* rho;
+    DevState* st;
+    int64_t entries_cap;
+    uint32_t merge_max, w_max;
+};
+
+template <typename T>
+__device__ inline bool merge_alive(const MergeArgs<T>& a, uint2 e, uint32_t s) {
+    return (e.x >> 30) == s && a.sp[s].id[e.x & 0x3FFFFFFFu] == e.y;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_merge_pick(MergeArgs<T> a) {
+    const int64_t total = a.off[a.g.nkeys];
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < a.entries_cap;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        if (b >= total) break;
+        const uint2 e = a.bins[b];
+        const uint32_t s = e.x >> 30;
+        uint32_t partner = kDead;
+        if (merge_alive(a, e, s)) {
+            const uint32_t k = a.key[s][e.x & 0x3FFFFFFFu];
+            const uint32_t o0 = a.off[k], o1 = a.off[k + 1];
+            uint32_t n = 0, r = 0, next_id = kDead, next_entry = kDead;
+            for (uint32_t j = o0; j < o1; ++j) {
+                const uint2 f = a.bins[j];
+                if (!merge_alive(a, f, s)) continue;
+                ++n;
+                if (f.y < e.y) ++r;
+                if (f.y > e.y && f.y < next_id) {
+                    next_id = f.y;
+                    next_entry = j;
+                }
+            }
+            if (n > a.merge_max && (r & 1u) == 0u) {
+                const uint32_t pairs = min(n / 2, n - a.merge_max);
+                if (r / 2 < pairs) partner = next_entry;
+            }
+        }
+        a.pick[b] = partner;
+    }
+}
+
+// adds sg charges at (X, Y, Z) with the quantized CIC weights of the deposit
+__device__ inline void deposit_one(const Grid& g, unsigned long long* rho, double X, double Y, double Z,
+                                   int64_t sg) {
+    const int ci = clampi((int)floor(X), 0, g.nx - 2), cj = clampi((int)floor(Y), 0, g.ny - 2),
+              ck = clampi((int)floor(Z), 0, g.nz - 2);
+    const int64_t qx = quantize(X - ci, 13), qy = quantize(Y - cj, 13), qz = quantize(Z - ck, 14);
+    const int64_t w[2][3] = {{8192 - qx, 8192 - qy, 16384 - qz}, {qx, qy, qz}};
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int dx = t & 1, dy = (t >> 1) & 1, dz = (t >> 2) & 1;
+        const int64_t v = sg * w[dx][0] * w[dy][1] * w[dz][2];
+        atomicAdd(rho + ((int64_t)(ck + dz) * g.ny + cj + dy) * g.nx + ci + dx, (unsigned long long)v);
+    }
+}
+
+// (wa a + wb b) / (wa + wb), evaluated as written (no contraction)
+__device__ inline double merge_mean(double wa, double va, double wb, double vb) {
+#pragma clang fp contract(off)
+    return (wa * va + wb * vb) / (wa + wb);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_merge_apply(MergeArgs<T> a) {
+    const int64_t total = a.off[a.g.nkeys];
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < a.entries_cap;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        if (b >= total) break;
+        const uint32_t j = a.pick[b];
+        if (j == kDead) continue;
+        const uint2 e = a.bins[b];
+        const uint32_t s = e.x >> 30;
+        const uint32_t i = e.x & 0x3FFFFFFFu, p = a.bins[j].x & 0x3FFFFFFFu;
+        const Species<T>& P = a.sp[s];
+        const uint32_t wa = P.w[i], wb = P.w[p];
+        if ((uint64_t)wa + wb > (uint64_t)a.w_max) continue;
+        const double fa = (double)wa, fb = (double)wb;
+        const double xa = (double)P.x[i], ya = (double)P.y[i], za = (double)P.z[i];
+        const double xb = (double)P.x[p], yb = (double)P.y[p], zb = (double)P.z[p];
+        const T xm = (T)merge_mean(fa, xa, fb, xb), ym = (T)merge_mean(fa, ya, fb, yb),
+                zm = (T)merge_mean(fa, za, fb, zb);
+        P.vx[i] = (T)merge_mean(fa, (double)P.vx[i], fb, (double)P.vx[p]);
+        P.vy[i] = (T)merge_mean(fa, (double)P.vy[i], fb, (double)P.vy[p]);
+        P.vz[i] = (T)merge_mean(fa, (double)P.vz[i], fb, (double)P.vz[p]);
+        P.x[i] = xm;
+        P.y[i] = ym;
+        P.z[i] = zm;
+        P.w[i] = wa + wb;
+        P.id[p] = kDead;
+        atomicAdd(&a.st->merges[s], 1ull);
+        if (s != PIC_NEUTRAL) {
+            const int64_t sg = s == PIC_ELECTRON ? -1 : 1;
+            unsigned long long* rho = (unsigned long long*)a.rho;
+            deposit_one(a.g, rho, xa, ya, za, -sg * (int64_t)wa);
+            deposit_one(a.g, rho, xb, yb, zb, -sg * (int64_t)wb);
+            deposit_one(a.g, rho, (double)xm, (double)ym, (double)zm, sg * ((int64_t)wa + wb));
+        }
+    }
+}
+
 template <typename T>
 static hipError_t collide_t(pic_ctx* c, bool record) {
     const pic_config& cf = c->cfg;
@@ -1557,6 +1679,23 @@ static hipError_t collide_t(pic_ctx* c, bool record) {
             hipLaunchKernelGGL(k_splits_clear<T>, dim3(grid_for(c->buf.cap[s])), dim3(kBlock), 0, c->stream, sa, s);
         hipLaunchKernelGGL(k_splits_finish, dim3(1), dim3(1), 0, c->stream, c->st, c->buf.cap[0], c->buf.cap[1],
                            c->buf.cap[2]);
+    }
+    if (merge_step(c)) {
+        MergeArgs<T> ma;
+        for (int s = 0; s < 3; ++s) ma.sp[s] = species<T>(c, s);
+        ma.g = g;
+        ma.off = c->off;
+        ma.bins = c->bins;
+        for (int s = 0; s < 3; ++s) ma.key[s] = c->key[s];
+        ma.pick = c->rank_flag;
+        ma.rho = c->buf.rho;
+        ma.st = c->st;
+        ma.entries_cap = c->buf.cap[0] + c->buf.cap[1] + c->buf.cap[2];
+        ma.merge_max = (uint32_t)cf.merge_max;
+        ma.w_max = (uint32_t)(cf.w_max > 1 ? cf.w_max : 1);
+        const unsigned G = grid_for(ma.entries_cap);
+        hipLaunchKernelGGL(k_merge_pick<T>, dim3(G), dim3(kBlock), 0, c->stream, ma);
+        hipLaunchKernelGGL(k_merge_apply<T>, dim3(G), dim3(kBlock), 0, c->stream, ma);
     }
     if (resort) {
         uint32_t* flag = c->rank_flag;

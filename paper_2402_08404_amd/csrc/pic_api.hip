@@ -92,6 +92,9 @@ const char* check_config(const pic_config* cfg) {
     if (cfg->surface_T > 0.0 && cfg->fn_rings == 0) return "evaporation needs the surface patches (fn_rings, fn_az)";
     if (cfg->weighted != 0 && cfg->weighted != 1) return "weighted must be 0 or 1";
     if (cfg->weighted && cfg->w_max > 1 && !(cfg->n_max > 0.0)) return "the injection weight rule needs n_max > 0";
+    if (cfg->merge_every < 0) return "merge_every must be >= 0";
+    if (cfg->merge_every > 0 && !cfg->weighted) return "merging needs weighted = 1";
+    if (cfg->merge_every > 0 && cfg->merge_max < 1) return "merging needs merge_max >= 1";
     return nullptr;
 }
 
@@ -545,7 +548,9 @@ pic_status pic_step(pic_ctx* c, int32_t nsteps, uint32_t flags) {
         // only the charge (already deposited), the potential and the field,
         // so without profiling a step that does both runs its collisions on
         // the side stream, concurrently with the solve.
-        const bool side = !c->prof && (flags & PIC_STEP_COLLIDE) && (flags & PIC_STEP_SOLVE);
+        // A step that merges superparticles corrects the charge after its
+        // collisions, so its solve waits for them.
+        const bool side = !c->prof && (flags & PIC_STEP_COLLIDE) && (flags & PIC_STEP_SOLVE) && !merge_step(c);
         bool joined = true;
         if (s == PIC_OK && (flags & PIC_STEP_COLLIDE)) {
             if (!c->bins_valid) return fail(c, PIC_E_INVALID_ARG, "the collide phase needs a push or deposit phase first");
@@ -654,6 +659,7 @@ pic_status pic_moments(pic_ctx* c, pic_moments_t* out) {
     for (int k = 0; k < 5; ++k) out->events_w[k] = (int64_t)h->events_w[k];
     out->splits = (int64_t)h->splits;
     out->evap_atoms = (int64_t)h->evap_atoms;
+    for (int s = 0; s < 3; ++s) out->merges[s] = (int64_t)h->merges[s];
     return s;
 }
 

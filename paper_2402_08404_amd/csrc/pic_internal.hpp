@@ -71,6 +71,7 @@ struct DevState {
     unsigned long long n_split[3];     // superparticles split off in this collide phase, per species
     unsigned long long splits;         // cumulative split-offs
     unsigned long long evap_atoms;     // cumulative evaporated atoms
+    unsigned long long merges[3];      // cumulative merged pairs per species
 };
 
 // Cells are numbered tile-major: tiles of kTile^3 cells, tile index
@@ -469,6 +470,10 @@ struct pic_ctx {
 };
 
 namespace pic {
+// the collide phase of this step merges superparticles
+inline bool merge_step(const pic_ctx* c) {
+    return c->cfg.merge_every > 0 && c->step % c->cfg.merge_every == 0;
+}
 // target block count of the z-marching solver kernels
 inline int stencil_target(const pic_ctx* c) { return c->cfg.stencil_blocks ? c->cfg.stencil_blocks : 1024; }
 size_t scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[3], char* base);
