@@ -30,10 +30,7 @@ struct PushArgs {
     T kq;
     int64_t* rho;
     int64_t sign;
-    uint32_t* key;
-    uint32_t* cnt;   // particles per cell key (nkeys entries), incremented here
-    uint32_t* rank;  // rank of each slot among the particles of its cell key
-    uint32_t nkeys;
+    uint32_t* key;   // cell key of each slot (kDead: no particle), binned by binning.hip
     DevState* st;
     uint32_t step;
     uint64_t seed;
@@ -88,9 +85,8 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs<T> a) {
     // and the Shockley-Ramo sum of the pushed charges (Sec. 2.3.1)
     double bomb[2] = {0.0, 0.0};
     double sr = 0.0;
-    // Every wavefront runs the loop the same number of times (lanes past the
-    // last slot load the last slot and store nothing), so that all lanes take
-    // part in the count of the keys.
+    // Lanes past the last slot load the last slot and store nothing, so the
+    // loads need no branch.
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += stride) {
         const int64_t i = base + threadIdx.x;
         const bool valid = i < n;
@@ -130,11 +126,7 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs<T> a) {
         const int ck = clampi((int)floor(Zd), 0, g.nz - 2);
         const bool keep = alive && code == 0;
         const uint32_t key = keep ? cell_key(g, ci, cj, ck) : kDead;
-        const uint32_t rk = count_key(a.cnt, a.nkeys, key);
-        if (valid) {
-            a.key[i] = key;
-            a.rank[i] = rk;
-        }
+        if (valid) a.key[i] = key;
         if (!alive) continue;
         if (MOVE) {
             if (SP != PIC_NEUTRAL) {
@@ -1382,9 +1374,6 @@ static hipError_t particles_t(pic_ctx* c, bool move) {
     const pic_config& cf = c->cfg;
     hipLaunchKernelGGL(k_step_reset, dim3(1), dim3(1), 0, c->stream, c->st);
     (void)launch_zero(c->buf.rho, sizeof(int64_t) * c->g.nn, c->stream);
-    // the pushes count the particles per cell key into off (see cell_bins)
-    hipError_t ez = launch_zero(c->off, ((size_t)c->g.nkeys + 1) * 4, c->stream);
-    if (ez != hipSuccess) return ez;
     for (int s = 0; s < 3; ++s) {
         PushArgs<T> a;
         a.s = species<T>(c, s);
@@ -1394,9 +1383,6 @@ static hipError_t particles_t(pic_ctx* c, bool move) {
         a.rho = c->buf.rho;
         a.sign = s == PIC_ELECTRON ? -1 : 1;
         a.key = c->key[s];
-        a.cnt = c->off;
-        a.rank = c->rank + (s >= 1 ? c->buf.cap[0] : 0) + (s == 2 ? c->buf.cap[1] : 0);
-        a.nkeys = (uint32_t)c->g.nkeys;
         a.st = c->st;
         a.step = (uint32_t)c->step;
         a.seed = cf.seed;

@@ -60,10 +60,29 @@ double adk_rate(double c, double e, double x32, double E) {
     return c * std::pow(20.5 * x32 / E, e) * std::exp(-6.83 * x32 / E);
 }
 
+// Groups of the binning: 2^s consecutive tiles with s the smallest that
+// leaves at most kBinTargetGroups groups, but no group above
+// kBinMaxCellsPerGroup cells; false if that leaves more than kBinMaxGroups.
+bool bin_groups(int64_t ntiles, int* ng, int* gshift) {
+    int sh = 0;
+    while (((ntiles + (1 << sh) - 1) >> sh) > kBinTargetGroups && (kTileCells << (sh + 1)) <= kBinMaxCellsPerGroup)
+        ++sh;
+    *ng = (int)((ntiles + (1 << sh) - 1) >> sh);
+    *gshift = 9 + sh;
+    return *ng <= kBinMaxGroups;
+}
+
 const char* check_config(const pic_config* cfg) {
     if (!cfg) return "config is NULL";
     if (cfg->nx < 4 || cfg->ny < 4 || cfg->nz < 4) return "nx, ny, nz must be >= 4";
     if ((int64_t)cfg->nx * cfg->ny * cfg->nz >= (int64_t)1 << 31) return "grid too large";
+    {
+        const int64_t ntiles =
+            (int64_t)((cfg->nx - 2) / kTile + 1) * ((cfg->ny - 2) / kTile + 1) * ((cfg->nz - 2) / kTile + 1);
+        int ng = 0, gshift = 0;
+        if (!bin_groups(ntiles, &ng, &gshift))
+            return "grid too large for the cell binning (over 131072 tiles of 8^3 cells)";
+    }
     if (!(cfg->h > 0) || !(cfg->dt > 0)) return "h and dt must be positive";
     if (!(cfg->tip_r > 0) || !(cfg->tip_h >= cfg->tip_r)) return "need tip_r > 0 and tip_h >= tip_r";
     double R = cfg->tip_r / cfg->h, H = cfg->tip_h / cfg->h;
@@ -178,6 +197,18 @@ size_t pic::scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[
     t->scan_blocks = (uint32_t*)take(scan_blocks * 4);
     t->rank_flag = (uint32_t*)take(capsum * 4);
     t->rank = (uint32_t*)take(capsum * 4);
+    {
+        int ng = 1, gshift = 9;
+        bin_groups(ntiles, &ng, &gshift);
+        int64_t nchunk = 0;
+        for (int s = 0; s < 3; ++s) nchunk += (cap[s] + kBinChunk - 1) / kBinChunk;
+        t->bin_hist = (uint32_t*)take(std::max<int64_t>(nchunk, 1) * ng * 4);
+        t->bin_segtot = (uint32_t*)take((int64_t)kBinSegments * ng * 4);
+        t->bin_gbase = (uint32_t*)take(((int64_t)ng + 1) * 4);
+        t->bin_stage = (uint4*)take(capsum * 16);
+        t->bin_ng = ng;
+        t->bin_gshift = gshift;
+    }
     t->tmp = take(capmax * (6 * tsz + 8));  // six state arrays, ids, weights
     t->cg_r = (double*)take(nn * 8);
     t->cg_p0 = (double*)take(nn * 8);

@@ -79,6 +79,14 @@ struct DevState {
 // + lx. nkeys = ntiles * kTile^3 >= nc (edge tiles may be partial).
 constexpr int kTile = 8;
 constexpr int kTileCells = kTile * kTile * kTile;
+// binning (binning.hip): slots per chunk, wanted and largest group count
+// (the LDS histogram of a chunk), largest group in cells, segments of the
+// column scan
+constexpr int kBinChunk = 32768;
+constexpr int kBinTargetGroups = 4096;
+constexpr int kBinMaxGroups = 16384;
+constexpr int kBinMaxCellsPerGroup = 4096;
+constexpr int kBinSegments = 32;
 
 struct Grid {
     int nx, ny, nz;
@@ -193,44 +201,6 @@ __device__ inline int64_t xcd_block(int64_t b, int64_t G) {
     int64_t per = G / 8, rem = G % 8;
     int64_t x = b % 8, t = b / 8;
     return x * per + (x < rem ? x : rem) + t;
-}
-
-// Runs of equal keys inside a wavefront: the run's first lane (head), the
-// run length (at the head) and every lane's offset inside its run.
-struct Run {
-    bool head;
-    int first, len;
-};
-
-__device__ inline Run wave_run(uint32_t k) {
-    const int lane = threadIdx.x & 63;
-    const uint32_t kp = __shfl_up(k, 1);
-    const bool head = lane == 0 || k != kp;
-    const unsigned long long heads = __ballot(head);
-    Run r;
-    r.head = head;
-    // first = the highest head at or below this lane
-    const unsigned long long below = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1));
-    r.first = 63 - __clzll(below);
-    // len (valid at a head) = distance to the next head, or to the wave end
-    const unsigned long long above = lane == 63 ? 0ull : (heads & ~((2ull << lane) - 1));
-    const int next = above ? __ffsll((long long)above) - 1 : 64;
-    r.len = next - lane;
-    return r;
-}
-
-// cnt[k] += 1 for the key k of every lane (keys >= nkeys count nothing), one
-// atomic per run of equal keys; every lane of the wavefront takes part.
-// Returns the lane's rank among the keys k counted so far (the count before
-// its run plus its place in the run), so a key's ranks are 0 .. cnt[k] - 1
-// once every lane has counted; undefined for keys that count nothing.
-__device__ inline uint32_t count_key(uint32_t* cnt, uint32_t nkeys, uint32_t k) {
-    if (k >= nkeys) k = kDead;
-    const Run r = wave_run(k);
-    uint32_t base = 0;
-    if (r.head && k != kDead) base = atomicAdd(&cnt[k], (uint32_t)r.len);
-    base = __shfl(base, r.first);
-    return base + (uint32_t)((int)(threadIdx.x & 63) - r.first);
 }
 
 // z-marching tiles for stencils on a node grid: blocks of 64 x 4 threads over
@@ -409,6 +379,11 @@ struct pic_ctx {
     int64_t scan_blocks_n = 0;
     uint32_t* dyn = nullptr;      // small device-side counts (scan lengths and totals)
     uint32_t** id_ptrs = nullptr; // device copy of the three id array pointers
+    uint32_t* bin_hist = nullptr;   // binning: [chunk][group] counts
+    uint32_t* bin_segtot = nullptr; // [segment][group] totals
+    uint32_t* bin_gbase = nullptr;  // [group + 1] first bins
+    uint4* bin_stage = nullptr;     // elements in group order (sum cap)
+    int bin_ng = 0, bin_gshift = 9; // groups, log2 of the cells per group
     uint32_t* rank_flag = nullptr;
     uint32_t* rank = nullptr;     // reorder destination ranks (per bin entry)
     void* tmp = nullptr;          // reorder staging: 6 arrays of tmp_cap elements + ids
