@@ -26,7 +26,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 SP_E, SP_ION, SP_NEU = 0, 1, 2
 FREE, DIR0, DIRV = 0, 1, 2
-COLL_MCC1, COLL_MCC2, COLL_FI = 1, 2, 4
+COLL_MCC1, COLL_MCC2, COLL_FI, COLL_NN, COLL_COUL = 1, 2, 4, 8, 16
 COLL_ALL = 7
 ALIVE, CATHODE, ANODE, LATERAL, TIP = 0, 1, 2, 3, 4
 KIND_ELASTIC, KIND_IONIZE, KIND_CX, KIND_FI = 1, 2, 3, 4
@@ -51,7 +51,7 @@ class _Config(C.Structure):
                 ("xs_el", C.POINTER(C.c_double)), ("xs_iz", C.POINTER(C.c_double)),
                 ("xs_cx", C.POINTER(C.c_double)), ("seed", C.c_uint64),
                 ("fn_rings", C.c_int32), ("fn_az", C.c_int32), ("w_max", C.c_int32), ("pad", C.c_int32),
-                ("n_max", C.c_double)]
+                ("n_max", C.c_double), ("sigma_nn", C.c_double), ("coulomb_log", C.c_double)]
 
 
 class _Species(C.Structure):
@@ -172,7 +172,8 @@ def make_config(cfg) -> tuple[_Config, list]:
                 xs_emin=cfg.xs_emin, xs_emax=cfg.xs_emax,
                 xs_el=keep[0].ctypes.data_as(dpp), xs_iz=keep[1].ctypes.data_as(dpp),
                 xs_cx=keep[2].ctypes.data_as(dpp), seed=cfg.seed, fn_rings=cfg.fn_rings, fn_az=cfg.fn_az,
-                w_max=int(getattr(cfg, "w_max", 1)), n_max=float(getattr(cfg, "n_max", 1e24)))
+                w_max=int(getattr(cfg, "w_max", 1)), n_max=float(getattr(cfg, "n_max", 1e24)),
+                sigma_nn=float(getattr(cfg, "sigma_nn", 0.0)), coulomb_log=float(getattr(cfg, "coulomb_log", 10.0)))
     return c, keep
 
 
@@ -454,6 +455,8 @@ class Oracle:
         self.V_gap = self.V_gap + cfg.dt / cfg.circuit_C * (self.i_tot - i_gap)
 
     def collide(self, flags: int = COLL_ALL):
+        if flags & (COLL_NN | COLL_COUL) and any((st.w[: st.n] != 1).any() for st in self.sp):
+            raise ValueError("same-species and Coulomb pairing are defined for unweighted particles")
         n_neu = self.sp[SP_NEU].n
         # room for the products (one ion and one electron per neutral) and for
         # a split-off superparticle of every particle
@@ -534,8 +537,16 @@ class Oracle:
             st.keep(~gone)
         return done
 
-    def step(self, rtol: float = 1e-8, inject: bool = True, collide_flags: int = COLL_ALL,
+    def step_flags(self) -> int:
+        """Collision flags of a whole step: the three classes of the plain
+        method, plus Cu-Cu elastic (same_species bit 1) and Coulomb (bit 2)."""
+        ss = int(getattr(self.cfg, "same_species", 0))
+        return COLL_ALL | (COLL_NN if ss & 1 else 0) | (COLL_COUL if ss & 2 else 0)
+
+    def step(self, rtol: float = 1e-8, inject: bool = True, collide_flags: int | None = None,
              solve: bool = True):
+        if collide_flags is None:
+            collide_flags = self.step_flags()
         if inject:
             self.inject()
             self.evaporate()

@@ -848,9 +848,164 @@ static void mcc_class(const orc_config* c, uint32_t step, int cls, const entry* 
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* Same-species and Coulomb pairing (Table colls: elastic Cu + Cu, Coulomb
+ * collisions between all charged particles). The paper names the processes
+ * and cites Takizuka and Abe for the Coulomb collisions without restating
+ * them; the readings here:
+ *  - the particles of one species in a cell (those present before this
+ *    step's collisions, unweighted), in ascending id order, are rotated
+ *    cyclically by floor(U_c N) (U_c drawn per cell) and paired
+ *    consecutively: (q0, q1), (q2, q3), ...;
+ *  - Cu + Cu elastic: hard spheres of cross section sigma_nn, a pair
+ *    collides when U1 < P = 1 - exp(-u n sigma_nn dt) with n = N / h^3, and
+ *    scatters isotropically in its centre-of-mass frame (Eq. du with
+ *    theta' = acos(2 U3 - 1), phi' = 2 pi U4); neutrals that had an event
+ *    this step sit out, and with N odd the last one;
+ *  - Coulomb (Takizuka-Abe): every pair scatters by theta = 2 atan(delta),
+ *    delta normal with variance q_a^2 q_b^2 n_L ln(Lambda) dt /
+ *    (8 pi eps0^2 mu^2 u^3), phi' uniform, applied through Eq. du; for the
+ *    same species n_L = N / h^3, and with N odd the first three particles
+ *    collide pairwise ((q0,q1), (q1,q2), (q2,q0)) with dt / 2 each; between
+ *    electrons and ions the more numerous species' particles, in ascending id
+ *    order, meet the other species' particles in ascending id order shifted
+ *    cyclically by floor(U_c N_f) (so those are reused, one after another),
+ *    with n_L the smaller density; a pair with u = 0 does not scatter. */
+#define TAG_PAIR_NN 8u
+#define TAG_NN 9u
+#define TAG_PAIR_EE 10u
+#define TAG_PAIR_II 11u
+#define TAG_PAIR_EI 12u
+#define TAG_COUL 13u
+#define TAG_COUL_EI 14u
+
+/* One Takizuka-Abe scattering of a (species sa, index ia) with (sb, ib) over
+ * a time dts at the density n_l; draws keyed by (subject, step, tag). */
+static void ta_scatter(const orc_config* c, uint32_t step, uint32_t subject, uint32_t tag, orc_species* A, int sa,
+                       int64_t ia, orc_species* B, int sb, int64_t ib, double n_l, double dts) {
+    double h = c->h, dt = c->dt;
+    double ma = (sa == ORC_SP_E) ? M_EL : c->m_ion, mb = (sb == ORC_SP_E) ? M_EL : c->m_ion;
+    double qa = (sa == ORC_SP_E) ? -E_CH : E_CH, qb = (sb == ORC_SP_E) ? -E_CH : E_CH;
+    double mu = ma * mb / (ma + mb);
+    double u[3] = {(A->vx[ia] - B->vx[ib]) * h / dt, (A->vy[ia] - B->vy[ib]) * h / dt,
+                   (A->vz[ia] - B->vz[ib]) * h / dt};
+    double um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    if (!(um > 0.0)) return;
+    double var = qa * qa * qb * qb * n_l * c->coulomb_log * dts / (8.0 * PI * EPS0 * EPS0 * mu * mu * um * um * um);
+    double u1, u2, u3, unused;
+    draw2(c, subject, step, tag, 0, &u1, &u2);
+    draw2(c, subject, step, tag, 1, &u3, &unused);
+    double delta = sqrt(var) * sqrt(-2.0 * log(u1)) * cos(2.0 * PI * u2);
+    double ct = (1.0 - delta * delta) / (1.0 + delta * delta);
+    double du[3];
+    elastic_du(u, ct, 2.0 * PI * u3, du);
+    double ka = mu / ma * dt / h, kb = mu / mb * dt / h;
+    A->vx[ia] += ka * du[0]; A->vy[ia] += ka * du[1]; A->vz[ia] += ka * du[2];
+    B->vx[ib] -= kb * du[0]; B->vy[ib] -= kb * du[1]; B->vz[ib] -= kb * du[2];
+}
+
+/* kind 0: Cu-Cu elastic; 1: e-e Coulomb; 2: Cu+-Cu+ Coulomb */
+static void pair_same(const orc_config* c, uint32_t step, int kind, const entry* ent, int64_t ne, orc_species* sp,
+                      uint8_t* used[3]) {
+    int s = kind == 0 ? ORC_SP_NEU : (kind == 1 ? ORC_SP_E : ORC_SP_ION);
+    uint32_t tpair = kind == 0 ? TAG_PAIR_NN : (kind == 1 ? TAG_PAIR_EE : TAG_PAIR_II);
+    orc_species* S = &sp[s];
+    double vol = c->h * c->h * c->h, h = c->h, dt = c->dt;
+    int64_t* q = malloc((ne + 1) * sizeof(int64_t));
+    int64_t s0 = 0;
+    while (s0 < ne) {
+        int64_t s1 = s0;
+        while (s1 < ne && ent[s1].cell == ent[s0].cell) ++s1;
+        int64_t a0 = s0;
+        while (a0 < s1 && ent[a0].sp != s) ++a0;
+        int64_t a1 = a0;
+        while (a1 < s1 && ent[a1].sp == s) ++a1;
+        int64_t N = a1 - a0;
+        if (N >= 2) {
+            double uc, unused;
+            draw2(c, (uint32_t)ent[s0].cell, step, tpair, 0, &uc, &unused);
+            int64_t shift = (int64_t)floor(uc * (double)N);
+            if (shift > N - 1) shift = N - 1;
+            for (int64_t j = 0; j < N; ++j) q[j] = ent[a0 + (shift + j) % N].idx;
+            double n = (double)N / vol;
+            if (kind == 0) {
+                for (int64_t j = 0; j + 1 < N; j += 2) {
+                    int64_t ia = q[j], ib = q[j + 1];
+                    if (used[s][ia] || used[s][ib]) continue;
+                    double u[3] = {(S->vx[ia] - S->vx[ib]) * h / dt, (S->vy[ia] - S->vy[ib]) * h / dt,
+                                   (S->vz[ia] - S->vz[ib]) * h / dt};
+                    double um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                    double P = -expm1(-um * n * c->sigma_nn * dt);
+                    double U1, unused2, u3, u4;
+                    draw2(c, S->id[ia], step, TAG_NN, 0, &U1, &unused2);
+                    if (!(U1 < P)) continue;
+                    draw2(c, S->id[ia], step, TAG_NN, 1, &u3, &u4);
+                    double du[3];
+                    elastic_du(u, 2.0 * u3 - 1.0, 2.0 * PI * u4, du);
+                    double k = 0.5 * dt / h;   /* mu / m = 1/2 */
+                    S->vx[ia] += k * du[0]; S->vy[ia] += k * du[1]; S->vz[ia] += k * du[2];
+                    S->vx[ib] -= k * du[0]; S->vy[ib] -= k * du[1]; S->vz[ib] -= k * du[2];
+                }
+            } else {
+                int64_t j0 = 0;
+                if (N % 2 == 1) {
+                    /* the first three pairwise with half the time step */
+                    ta_scatter(c, step, S->id[q[0]], TAG_COUL, S, s, q[0], S, s, q[1], n, 0.5 * dt);
+                    ta_scatter(c, step, S->id[q[1]], TAG_COUL, S, s, q[1], S, s, q[2], n, 0.5 * dt);
+                    ta_scatter(c, step, S->id[q[2]], TAG_COUL, S, s, q[2], S, s, q[0], n, 0.5 * dt);
+                    j0 = 3;
+                }
+                for (int64_t j = j0; j + 1 < N; j += 2)
+                    ta_scatter(c, step, S->id[q[j]], TAG_COUL, S, s, q[j], S, s, q[j + 1], n, dt);
+            }
+        }
+        s0 = s1;
+    }
+    free(q);
+}
+
+static void coulomb_e_ion(const orc_config* c, uint32_t step, const entry* ent, int64_t ne, orc_species* sp) {
+    double vol = c->h * c->h * c->h, dt = c->dt;
+    int64_t s0 = 0;
+    while (s0 < ne) {
+        int64_t s1 = s0;
+        while (s1 < ne && ent[s1].cell == ent[s0].cell) ++s1;
+        int64_t e0 = s0;
+        while (e0 < s1 && ent[e0].sp != ORC_SP_E) ++e0;
+        int64_t e1 = e0;
+        while (e1 < s1 && ent[e1].sp == ORC_SP_E) ++e1;
+        int64_t i0 = s0;
+        while (i0 < s1 && ent[i0].sp != ORC_SP_ION) ++i0;
+        int64_t i1 = i0;
+        while (i1 < s1 && ent[i1].sp == ORC_SP_ION) ++i1;
+        int64_t NE = e1 - e0, NI = i1 - i0;
+        if (NE > 0 && NI > 0) {
+            /* the more numerous species meets the other (tie: electrons meet ions) */
+            int e_more = NE >= NI;
+            int64_t M0 = e_more ? e0 : i0, NM = e_more ? NE : NI;
+            int64_t F0 = e_more ? i0 : e0, NF = e_more ? NI : NE;
+            double uc, unused;
+            draw2(c, (uint32_t)ent[s0].cell, step, TAG_PAIR_EI, 0, &uc, &unused);
+            int64_t shift = (int64_t)floor(uc * (double)NF);
+            if (shift > NF - 1) shift = NF - 1;
+            double n_l = (double)NF / vol;
+            for (int64_t i = 0; i < NM; ++i) {
+                const entry* m = &ent[M0 + i];
+                const entry* f = &ent[F0 + (shift + i) % NF];
+                const entry* ee = e_more ? m : f;
+                const entry* ei = e_more ? f : m;
+                ta_scatter(c, step, m->id, TAG_COUL_EI, &sp[ORC_SP_E], ORC_SP_E, ee->idx, &sp[ORC_SP_ION], ORC_SP_ION,
+                           ei->idx, n_l, dt);
+            }
+        }
+        s0 = s1;
+    }
+}
+
 /* Collisions of one step on the post-push state: (e,Cu) pairs, then (Cu+,Cu)
- * pairs, then field ionization of every neutral without an event, then the
- * products. Ionization products (impact and field) are created in the order
+ * pairs, then field ionization of every neutral without an event, then (with
+ * their flags) Cu-Cu elastic pairs, e-e, Cu+-Cu+ and e-Cu+ Coulomb pairs,
+ * then the products. Ionization products (impact and field) are created in the order
  * (impact before field, ascending neutral id), each taking two new ids: the ion
  * first, then the electron; each carries the N_coll ionized units, which the
  * neutral loses. Then the split-off superparticles, in the order (species,
@@ -917,6 +1072,13 @@ int orc_collide(const orc_config* c, uint32_t step, int32_t flags, const double*
                 o->n_kind_w[4] += ncoll;
             }
         }
+    }
+
+    if (flags & ORC_COLL_NN) pair_same(c, step, 0, ent, ne, sp, used);
+    if (flags & ORC_COLL_COUL) {
+        pair_same(c, step, 1, ent, ne, sp, used);
+        pair_same(c, step, 2, ent, ne, sp, used);
+        coulomb_e_ion(c, step, ent, ne, sp);
     }
 
     int rc = 0;

@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import test_oracle_merging as M
+import test_oracle_pairing as PR
 import test_oracle_readings as R
 import test_oracle_surface as S
 import test_oracle_weights as WT
@@ -75,6 +76,27 @@ MUTATIONS = [
     ("injection weight without the geometric mean",
      "double r = sqrt(n_cell / c->n_max * (double)n_inj);", "double r = n_cell / c->n_max * (double)n_inj;",
      WT.pin_injection_weights),
+    ("Cu-Cu collision probability without the density",
+     "double P = -expm1(-um * n * c->sigma_nn * dt);", "double P = -expm1(-um * c->sigma_nn * dt);",
+     PR.pin_nn_rate_and_isotropy),
+    ("Cu-Cu scattering not isotropic (cos theta' = U)",
+     "elastic_du(u, 2.0 * u3 - 1.0, 2.0 * PI * u4, du);\n                    double k = 0.5 * dt / h;",
+     "elastic_du(u, u3, 2.0 * PI * u4, du);\n                    double k = 0.5 * dt / h;", PR.pin_nn_rate_and_isotropy),
+    ("Cu-Cu kick without the reduced mass",
+     "double k = 0.5 * dt / h;   /* mu / m = 1/2 */", "double k = dt / h;", PR.pin_nn_rate_and_isotropy),
+    ("Takizuka-Abe variance with mu instead of mu^2",
+     "(8.0 * PI * EPS0 * EPS0 * mu * mu * um * um * um)", "(8.0 * PI * EPS0 * EPS0 * mu * um * um * um)",
+     PR.pin_coulomb_angle),
+    ("Takizuka-Abe variance with u^2 instead of u^3",
+     "(8.0 * PI * EPS0 * EPS0 * mu * mu * um * um * um)", "(8.0 * PI * EPS0 * EPS0 * mu * mu * um * um)",
+     PR.pin_coulomb_angle),
+    ("Takizuka-Abe angle theta = delta instead of 2 atan(delta)",
+     "double ct = (1.0 - delta * delta) / (1.0 + delta * delta);", "double ct = cos(delta);", PR.pin_coulomb_angle),
+    ("same-species pairs without the cyclic shift",
+     "for (int64_t j = 0; j < N; ++j) q[j] = ent[a0 + (shift + j) % N].idx;",
+     "for (int64_t j = 0; j < N; ++j) q[j] = ent[a0 + j].idx;", PR.pin_pairing_enumerated),
+    ("e-Cu+ Coulomb with the larger density",
+     "double n_l = (double)NF / vol;", "double n_l = (double)NM / vol;", PR.pin_coulomb_e_ion),
 ]
 
 
