@@ -140,6 +140,19 @@ typedef struct pic_config {
      * exactly (integer deposit), and such a step runs its collisions before the solve. */
     int32_t merge_every;   /* 0: no merging */
     int32_t merge_max;     /* >= 1 when merge_every > 0 */
+    /* Same-species and Coulomb pairing (Table colls: Cu + Cu elastic, Coulomb collisions of all charged
+     * particles after Takizuka and Abe; needs weighted = 0): in the collide phase, after the collisions
+     * and products, per cell the particles of one species binned by the push, in ascending id order
+     * rotated by floor(U_c N), are paired consecutively. Cu + Cu: hard spheres of cross section
+     * sigma_nn, P = 1 - exp(-u n sigma_nn dt), n = N / h^3, isotropic scattering; neutrals with an event
+     * this step and, for odd N, the last one sit out. Coulomb: every pair's relative velocity turns by
+     * 2 atan(delta), delta normal of variance e^4 n_L ln(Lambda) dt / (8 pi eps0^2 mu^2 u^3); odd N: the
+     * first three collide pairwise with dt / 2; e-Cu+: each particle of the more numerous species meets
+     * one of the other (reused cyclically), n_L the smaller density. */
+    int32_t same_species;  /* bit 0: Cu + Cu elastic, bit 1: Coulomb; 0: neither */
+    int32_t reserved2;
+    double sigma_nn;       /* Cu-Cu elastic cross section [m^2] */
+    double coulomb_log;    /* Coulomb logarithm ln(Lambda), > 0 with the Coulomb bit */
 } pic_config;
 
 typedef struct pic_buffers {
@@ -217,6 +230,8 @@ typedef struct pic_moments_t {
     int64_t splits;            /* cumulative superparticles split off by partial collisions */
     int64_t evap_atoms;        /* cumulative evaporated atoms (the weights of the evaporated neutrals) */
     int64_t merges[3];         /* cumulative merged pairs per species */
+    int64_t nn_events;         /* cumulative Cu + Cu elastic collisions */
+    int64_t coulomb_pairs;     /* cumulative Coulomb scatterings (pairs with u > 0) */
 } pic_moments_t;
 
 typedef struct pic_event {

@@ -69,7 +69,7 @@ class _CollideOut(C.Structure):
     _fields_ = [("ev", C.POINTER(_Event)), ("ev_cap", C.c_int64), ("n_ev", C.c_int64),
                 ("fragile", C.POINTER(C.c_uint32)), ("fr_cap", C.c_int64), ("n_fragile", C.c_int64),
                 ("n_kind", C.c_int64 * 5), ("n_bsi_skip", C.c_int64), ("n_kind_w", C.c_int64 * 5),
-                ("n_split", C.c_int64)]
+                ("n_split", C.c_int64), ("n_nn", C.c_int64), ("n_coul", C.c_int64)]
 
 
 _lib = None
@@ -298,6 +298,8 @@ class Oracle:
         self.events_w = np.zeros(5, np.int64)     # physical collisions per kind (sum of N_coll)
         self.splits = 0
         self.merges = np.zeros(3, np.int64)      # merged pairs per species
+        self.nn_events = 0                        # Cu-Cu elastic collisions
+        self.coulomb_pairs = 0                    # Coulomb scatterings
         self.last_events = []
         self.last_fragile = set()
         self.last_solve = (0, 0.0)
@@ -481,6 +483,8 @@ class Oracle:
             self.events[k] += out.n_kind[k]
             self.events_w[k] += out.n_kind_w[k]
         self.splits += int(out.n_split)
+        self.nn_events += int(out.n_nn)
+        self.coulomb_pairs += int(out.n_coul)
         self.bsi_skips += int(out.n_bsi_skip)
         return self.last_events
 
@@ -573,7 +577,8 @@ class Oracle:
                 "i_gap": self.i_gap, "i_tot": self.i_tot, "bomb_energy": self.bomb_energy.copy(),
                 "evaporated": self.evaporated, "evap_atoms": self.evap_atoms, "evap_expected": self.evap_expected,
                 "n_phys": np.array([int(st.w[: st.n].sum()) for st in self.sp], np.int64),
-                "events_w": self.events_w.copy(), "splits": self.splits, "merges": self.merges.copy()}
+                "events_w": self.events_w.copy(), "splits": self.splits, "merges": self.merges.copy(),
+                "nn_events": self.nn_events, "coulomb_pairs": self.coulomb_pairs}
 
     # -- helpers for tests ----------------------------------------------------
     def gather(self, E: np.ndarray, X, Y, Z) -> np.ndarray:

@@ -881,8 +881,8 @@ static void mcc_class(const orc_config* c, uint32_t step, int cls, const entry* 
 
 /* One Takizuka-Abe scattering of a (species sa, index ia) with (sb, ib) over
  * a time dts at the density n_l; draws keyed by (subject, step, tag). */
-static void ta_scatter(const orc_config* c, uint32_t step, uint32_t subject, uint32_t tag, orc_species* A, int sa,
-                       int64_t ia, orc_species* B, int sb, int64_t ib, double n_l, double dts) {
+static int ta_scatter(const orc_config* c, uint32_t step, uint32_t subject, uint32_t tag, orc_species* A, int sa,
+                      int64_t ia, orc_species* B, int sb, int64_t ib, double n_l, double dts) {
     double h = c->h, dt = c->dt;
     double ma = (sa == ORC_SP_E) ? M_EL : c->m_ion, mb = (sb == ORC_SP_E) ? M_EL : c->m_ion;
     double qa = (sa == ORC_SP_E) ? -E_CH : E_CH, qb = (sb == ORC_SP_E) ? -E_CH : E_CH;
@@ -890,7 +890,7 @@ static void ta_scatter(const orc_config* c, uint32_t step, uint32_t subject, uin
     double u[3] = {(A->vx[ia] - B->vx[ib]) * h / dt, (A->vy[ia] - B->vy[ib]) * h / dt,
                    (A->vz[ia] - B->vz[ib]) * h / dt};
     double um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    if (!(um > 0.0)) return;
+    if (!(um > 0.0)) return 0;
     double var = qa * qa * qb * qb * n_l * c->coulomb_log * dts / (8.0 * PI * EPS0 * EPS0 * mu * mu * um * um * um);
     double u1, u2, u3, unused;
     draw2(c, subject, step, tag, 0, &u1, &u2);
@@ -902,11 +902,14 @@ static void ta_scatter(const orc_config* c, uint32_t step, uint32_t subject, uin
     double ka = mu / ma * dt / h, kb = mu / mb * dt / h;
     A->vx[ia] += ka * du[0]; A->vy[ia] += ka * du[1]; A->vz[ia] += ka * du[2];
     B->vx[ib] -= kb * du[0]; B->vy[ib] -= kb * du[1]; B->vz[ib] -= kb * du[2];
+    return 1;
 }
 
-/* kind 0: Cu-Cu elastic; 1: e-e Coulomb; 2: Cu+-Cu+ Coulomb */
-static void pair_same(const orc_config* c, uint32_t step, int kind, const entry* ent, int64_t ne, orc_species* sp,
-                      uint8_t* used[3]) {
+/* kind 0: Cu-Cu elastic; 1: e-e Coulomb; 2: Cu+-Cu+ Coulomb. Returns the
+ * number of collisions (kind 0) or scatterings. */
+static int64_t pair_same(const orc_config* c, uint32_t step, int kind, const entry* ent, int64_t ne, orc_species* sp,
+                         uint8_t* used[3]) {
+    int64_t count = 0;
     int s = kind == 0 ? ORC_SP_NEU : (kind == 1 ? ORC_SP_E : ORC_SP_ION);
     uint32_t tpair = kind == 0 ? TAG_PAIR_NN : (kind == 1 ? TAG_PAIR_EE : TAG_PAIR_II);
     orc_species* S = &sp[s];
@@ -945,26 +948,29 @@ static void pair_same(const orc_config* c, uint32_t step, int kind, const entry*
                     double k = 0.5 * dt / h;   /* mu / m = 1/2 */
                     S->vx[ia] += k * du[0]; S->vy[ia] += k * du[1]; S->vz[ia] += k * du[2];
                     S->vx[ib] -= k * du[0]; S->vy[ib] -= k * du[1]; S->vz[ib] -= k * du[2];
+                    ++count;
                 }
             } else {
                 int64_t j0 = 0;
                 if (N % 2 == 1) {
                     /* the first three pairwise with half the time step */
-                    ta_scatter(c, step, S->id[q[0]], TAG_COUL, S, s, q[0], S, s, q[1], n, 0.5 * dt);
-                    ta_scatter(c, step, S->id[q[1]], TAG_COUL, S, s, q[1], S, s, q[2], n, 0.5 * dt);
-                    ta_scatter(c, step, S->id[q[2]], TAG_COUL, S, s, q[2], S, s, q[0], n, 0.5 * dt);
+                    count += ta_scatter(c, step, S->id[q[0]], TAG_COUL, S, s, q[0], S, s, q[1], n, 0.5 * dt);
+                    count += ta_scatter(c, step, S->id[q[1]], TAG_COUL, S, s, q[1], S, s, q[2], n, 0.5 * dt);
+                    count += ta_scatter(c, step, S->id[q[2]], TAG_COUL, S, s, q[2], S, s, q[0], n, 0.5 * dt);
                     j0 = 3;
                 }
                 for (int64_t j = j0; j + 1 < N; j += 2)
-                    ta_scatter(c, step, S->id[q[j]], TAG_COUL, S, s, q[j], S, s, q[j + 1], n, dt);
+                    count += ta_scatter(c, step, S->id[q[j]], TAG_COUL, S, s, q[j], S, s, q[j + 1], n, dt);
             }
         }
         s0 = s1;
     }
     free(q);
+    return count;
 }
 
-static void coulomb_e_ion(const orc_config* c, uint32_t step, const entry* ent, int64_t ne, orc_species* sp) {
+static int64_t coulomb_e_ion(const orc_config* c, uint32_t step, const entry* ent, int64_t ne, orc_species* sp) {
+    int64_t count = 0;
     double vol = c->h * c->h * c->h, dt = c->dt;
     int64_t s0 = 0;
     while (s0 < ne) {
@@ -994,12 +1000,13 @@ static void coulomb_e_ion(const orc_config* c, uint32_t step, const entry* ent, 
                 const entry* f = &ent[F0 + (shift + i) % NF];
                 const entry* ee = e_more ? m : f;
                 const entry* ei = e_more ? f : m;
-                ta_scatter(c, step, m->id, TAG_COUL_EI, &sp[ORC_SP_E], ORC_SP_E, ee->idx, &sp[ORC_SP_ION], ORC_SP_ION,
-                           ei->idx, n_l, dt);
+                count += ta_scatter(c, step, m->id, TAG_COUL_EI, &sp[ORC_SP_E], ORC_SP_E, ee->idx, &sp[ORC_SP_ION],
+                                    ORC_SP_ION, ei->idx, n_l, dt);
             }
         }
         s0 = s1;
     }
+    return count;
 }
 
 /* Collisions of one step on the post-push state: (e,Cu) pairs, then (Cu+,Cu)
@@ -1074,11 +1081,12 @@ int orc_collide(const orc_config* c, uint32_t step, int32_t flags, const double*
         }
     }
 
-    if (flags & ORC_COLL_NN) pair_same(c, step, 0, ent, ne, sp, used);
+    o->n_nn = 0; o->n_coul = 0;
+    if (flags & ORC_COLL_NN) o->n_nn = pair_same(c, step, 0, ent, ne, sp, used);
     if (flags & ORC_COLL_COUL) {
-        pair_same(c, step, 1, ent, ne, sp, used);
-        pair_same(c, step, 2, ent, ne, sp, used);
-        coulomb_e_ion(c, step, ent, ne, sp);
+        o->n_coul += pair_same(c, step, 1, ent, ne, sp, used);
+        o->n_coul += pair_same(c, step, 2, ent, ne, sp, used);
+        o->n_coul += coulomb_e_ion(c, step, ent, ne, sp);
     }
 
     int rc = 0;

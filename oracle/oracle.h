@@ -64,6 +64,8 @@ typedef struct orc_collide_out {
     int64_t n_bsi_skip;     /* neutrals above the barrier-suppression limit */
     int64_t n_kind_w[5];    /* physical collisions per kind (sum of N_coll over the events) */
     int64_t n_split;        /* superparticles split off by partial collisions */
+    int64_t n_nn;           /* Cu-Cu elastic collisions */
+    int64_t n_coul;         /* Coulomb scatterings (pairs with u > 0) */
 } orc_collide_out;
 
 enum { ORC_SP_E = 0, ORC_SP_ION = 1, ORC_SP_NEU = 2 };

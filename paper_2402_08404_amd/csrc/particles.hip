@@ -1435,6 +1435,283 @@ hipError_t particles_phase(pic_ctx* c, bool move) {
 }
 
 // ---------------------------------------------------------------------------
+// Same-species and Coulomb pairing (Table colls: Cu + Cu elastic, Coulomb
+// collisions of the charged particles), on the bins of the push after the
+// collisions and products of the step (unweighted runs). Per cell the
+// particles of a species, in ascending id order, are rotated by
+// floor(U_c N) (U_c from the cell, the step and the class) and paired
+// consecutively. Cu + Cu: hard spheres, P = 1 - exp(-u n sigma_nn dt),
+// n = N / h^3, isotropic scattering through Eq. du; neutrals with an event
+// this step (or removed by it) keep their place but their pair is void, and
+// with N odd the last one sits out. Coulomb (Takizuka-Abe): every pair turns
+// its relative velocity by theta = 2 atan(delta), delta normal with variance
+// e^4 n_L ln(Lambda) dt / (8 pi eps0^2 mu^2 u^3), through Eq. du; with N odd
+// the first three collide pairwise with dt / 2 each; between electrons and
+// ions each particle of the more numerous species meets one of the other,
+// whose particles are reused cyclically (shifted by floor(U_c N_f)), with n_L
+// the smaller density. Cells of up to kSmallCell particles take one thread;
+// larger ones (listed by the collision scan) a wavefront, whose lanes take
+// disjoint pairs.
+
+template <typename T>
+struct PairArgs {
+    Species<T> sp[3];
+    Grid g;
+    const uint32_t* off;
+    const uint2* bins;
+    const uint32_t* big;     // cells of more than kSmallCell particles (count st->n_big)
+    const uint32_t* nflag;   // neutral slot: step + 1 if it had an event this step
+    DevState* st;
+    uint32_t step;
+    uint64_t seed;
+    double h, dt, m_ion, sigma_nn, coulomb_log;
+    int nn, coul;
+    int64_t nc;
+};
+
+// Eq. du: Delta u = R^-1(theta, phi) [R^-1(theta', phi') - I] (0, 0, |u|)
+__device__ inline void eq_du(const double u[3], double um, double ct2, double ph2, double du[3]) {
+    const double up = sqrt(u[0] * u[0] + u[1] * u[1]);
+    const double ct = u[2] / um, st = up / um;
+    double cp = 1.0, sp = 0.0;
+    if (up > 0.0) {
+        cp = u[0] / up;
+        sp = u[1] / up;
+    }
+    const double st2 = sqrt(1.0 - ct2 * ct2);
+    double sp2, cp2;
+    sincos(ph2, &sp2, &cp2);
+    const double w0 = um * st2 * cp2, w1 = um * st2 * sp2, w2 = um * (ct2 - 1.0);
+    du[0] = ct * cp * w0 - sp * w1 + st * cp * w2;
+    du[1] = ct * sp * w0 + cp * w1 + st * sp * w2;
+    du[2] = -st * w0 + ct * w2;
+}
+
+// One Takizuka-Abe scattering of (sa, ia) with (sb, ib) over dts at the
+// density n_l, draws keyed by (subject, step, tag). Returns 1 if it turned.
+template <typename T>
+__device__ inline int ta_pair(const PairArgs<T>& a, uint32_t subject, uint32_t tag, int sa, uint32_t ia, int sb,
+                              uint32_t ib, double n_l, double dts) {
+    const Species<T>& A = a.sp[sa];
+    const Species<T>& B = a.sp[sb];
+    const double s = a.h / a.dt, g = a.dt / a.h;
+    const double ma = sa == PIC_ELECTRON ? kMe : a.m_ion, mb = sb == PIC_ELECTRON ? kMe : a.m_ion;
+    const double mu = ma * mb / (ma + mb);
+    const double vA[3] = {(double)A.vx[ia], (double)A.vy[ia], (double)A.vz[ia]};
+    const double vB[3] = {(double)B.vx[ib], (double)B.vy[ib], (double)B.vz[ib]};
+    const double u[3] = {(vA[0] - vB[0]) * s, (vA[1] - vB[1]) * s, (vA[2] - vB[2]) * s};
+    const double um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    if (!(um > 0.0)) return 0;
+    const double var =
+        kQe * kQe * kQe * kQe * n_l * a.coulomb_log * dts / (8.0 * kPi * kEps0 * kEps0 * mu * mu * um * um * um);
+    const Draw2 d0 = draw2(a.seed, subject, a.step, tag, 0);
+    const Draw2 d1 = draw2(a.seed, subject, a.step, tag, 1);
+    const double delta = sqrt(var) * sqrt(-2.0 * log(d0.a)) * cos(2.0 * kPi * d0.b);
+    const double ct = (1.0 - delta * delta) / (1.0 + delta * delta);
+    double du[3];
+    eq_du(u, um, ct, 2.0 * kPi * d1.a, du);
+    const double ka = mu / ma * g, kb = mu / mb * g;
+    A.vx[ia] = (T)(vA[0] + ka * du[0]);
+    A.vy[ia] = (T)(vA[1] + ka * du[1]);
+    A.vz[ia] = (T)(vA[2] + ka * du[2]);
+    B.vx[ib] = (T)(vB[0] - kb * du[0]);
+    B.vy[ib] = (T)(vB[1] - kb * du[1]);
+    B.vz[ib] = (T)(vB[2] - kb * du[2]);
+    return 1;
+}
+
+// One Cu + Cu pair (slots ia, ib with ids ida, idb); returns 1 on a collision
+template <typename T>
+__device__ inline int nn_pair(const PairArgs<T>& a, uint32_t ia, uint32_t ida, uint32_t ib, uint32_t idb, double n) {
+    const Species<T>& N = a.sp[PIC_NEUTRAL];
+    if (N.id[ia] != ida || N.id[ib] != idb) return 0;                       // removed by an event
+    if (a.nflag[ia] == a.step + 1u || a.nflag[ib] == a.step + 1u) return 0;  // had an event
+    const double s = a.h / a.dt, g = a.dt / a.h;
+    const double vA[3] = {(double)N.vx[ia], (double)N.vy[ia], (double)N.vz[ia]};
+    const double vB[3] = {(double)N.vx[ib], (double)N.vy[ib], (double)N.vz[ib]};
+    const double u[3] = {(vA[0] - vB[0]) * s, (vA[1] - vB[1]) * s, (vA[2] - vB[2]) * s};
+    const double um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const double P = -expm1(-um * n * a.sigma_nn * a.dt);
+    if (!(draw2(a.seed, ida, a.step, kTagNN, 0).a < P)) return 0;
+    const Draw2 r = draw2(a.seed, ida, a.step, kTagNN, 1);
+    double du[3];
+    eq_du(u, um, 2.0 * r.a - 1.0, 2.0 * kPi * r.b, du);
+    const double k = 0.5 * g;  // mu / m = 1/2
+    N.vx[ia] = (T)(vA[0] + k * du[0]);
+    N.vy[ia] = (T)(vA[1] + k * du[1]);
+    N.vz[ia] = (T)(vA[2] + k * du[2]);
+    N.vx[ib] = (T)(vB[0] - k * du[0]);
+    N.vy[ib] = (T)(vB[1] - k * du[1]);
+    N.vz[ib] = (T)(vB[2] - k * du[2]);
+    return 1;
+}
+
+__device__ inline int pair_shift(uint64_t seed, uint32_t lcell, uint32_t step, uint32_t tag, int N) {
+    const Draw2 dc = draw2(seed, lcell, step, tag, 0);
+    int sh = (int)floor(dc.a * (double)N);
+    return sh > N - 1 ? N - 1 : sh;
+}
+
+// The classes of one cell whose entries (species << 30 | slot, ids) are
+// sorted by (species, id): kv[t] = species << 32 | id, ev[t] = the value.
+// lane / lanes split the disjoint pairs (1 / 1 for one thread per cell);
+// sync() orders the rounds that reuse a particle.
+template <typename T, typename KV, typename EV, typename Sync>
+__device__ inline void pair_classes(const PairArgs<T>& a, uint32_t cell, const KV& kv, const EV& ev, int n, int lane,
+                                    int lanes, Sync sync, int cnt[2]) {
+    int b0[4] = {0, 0, 0, 0};
+    for (int t = 0; t < n; ++t) b0[(int)(kv(t) >> 32) + 1] = t + 1;
+    for (int s = 1; s < 4; ++s) b0[s] = b0[s] > b0[s - 1] ? b0[s] : b0[s - 1];
+    const uint32_t lc = linear_cell(a.g, cell);
+    const double vol = a.h * a.h * a.h;
+    const auto slot = [&](int t) { return ev(t) & 0x3FFFFFFFu; };
+    const auto idof = [&](int t) { return (uint32_t)(kv(t) & 0xFFFFFFFFu); };
+    if (a.nn) {
+        const int o = b0[PIC_NEUTRAL], N = b0[PIC_NEUTRAL + 1] - o;
+        if (N >= 2) {
+            const int sh = pair_shift(a.seed, lc, a.step, kTagPairNN, N);
+            const double n = (double)N / vol;
+            for (int j = 2 * lane; j + 1 < N; j += 2 * lanes) {
+                const int ta = o + (sh + j) % N, tb = o + (sh + j + 1) % N;
+                cnt[0] += nn_pair(a, slot(ta), idof(ta), slot(tb), idof(tb), n);
+            }
+            sync();
+        }
+    }
+    if (!a.coul) return;
+    for (int sp = PIC_ELECTRON; sp <= PIC_ION; ++sp) {
+        const int o = b0[sp], N = b0[sp + 1] - o;
+        if (N < 2) continue;
+        const int sh = pair_shift(a.seed, lc, a.step, sp == PIC_ELECTRON ? kTagPairEE : kTagPairII, N);
+        const double n = (double)N / vol;
+        const auto q = [&](int j) { return o + (sh + j) % N; };
+        int j0 = 0;
+        if (N % 2 == 1) {
+            if (lane == 0) {
+                cnt[1] += ta_pair(a, idof(q(0)), kTagCoul, sp, slot(q(0)), sp, slot(q(1)), n, 0.5 * a.dt);
+                cnt[1] += ta_pair(a, idof(q(1)), kTagCoul, sp, slot(q(1)), sp, slot(q(2)), n, 0.5 * a.dt);
+                cnt[1] += ta_pair(a, idof(q(2)), kTagCoul, sp, slot(q(2)), sp, slot(q(0)), n, 0.5 * a.dt);
+            }
+            sync();
+            j0 = 3;
+        }
+        for (int j = j0 + 2 * lane; j + 1 < N; j += 2 * lanes)
+            cnt[1] += ta_pair(a, idof(q(j)), kTagCoul, sp, slot(q(j)), sp, slot(q(j + 1)), n, a.dt);
+        sync();
+    }
+    const int oe = b0[PIC_ELECTRON], NE = b0[PIC_ELECTRON + 1] - oe;
+    const int oi = b0[PIC_ION], NI = b0[PIC_ION + 1] - oi;
+    if (NE > 0 && NI > 0) {
+        const bool e_more = NE >= NI;
+        const int oM = e_more ? oe : oi, NM = e_more ? NE : NI, oF = e_more ? oi : oe, NF = e_more ? NI : NE;
+        const int sh = pair_shift(a.seed, lc, a.step, kTagPairEI, NF);
+        const double n_l = (double)NF / vol;
+        // rounds of NF pairs: within a round every particle of the fewer
+        // species appears once
+        for (int r0 = 0; r0 < NM; r0 += NF) {
+            const int r1 = r0 + NF < NM ? r0 + NF : NM;
+            for (int i = r0 + lane; i < r1; i += lanes) {
+                const int tm = oM + i, tf = oF + (sh + i) % NF;
+                const int te = e_more ? tm : tf, ti = e_more ? tf : tm;
+                cnt[1] += ta_pair(a, idof(tm), kTagCoulEI, PIC_ELECTRON, slot(te), PIC_ION, slot(ti), n_l, a.dt);
+            }
+            sync();
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_pair_small(PairArgs<T> a) {
+    int cnt[2] = {0, 0};
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.nc; c += stride) {
+        const uint32_t o0 = a.off[c];
+        const int n = (int)(a.off[c + 1] - o0);
+        if (n < 2 || n > kSmallCell) continue;
+        uint64_t kk[kSmallCell];
+        uint32_t ee[kSmallCell];
+        for (int t = 0; t < n; ++t) {
+            const uint2 be = a.bins[o0 + t];
+            const uint64_t k = ((uint64_t)(be.x >> 30) << 32) | be.y;
+            int u = t;
+            while (u > 0 && kk[u - 1] > k) {
+                kk[u] = kk[u - 1];
+                ee[u] = ee[u - 1];
+                --u;
+            }
+            kk[u] = k;
+            ee[u] = be.x;
+        }
+        pair_classes(
+            a, (uint32_t)c, [&](int t) { return kk[t]; }, [&](int t) { return ee[t]; }, n, 0, 1, [] {}, cnt);
+    }
+    __shared__ int sh[kBlock / 64];
+    const int t0 = block_sum(cnt[0], sh);
+    const int t1 = block_sum(cnt[1], sh);
+    if (threadIdx.x == 0) {
+        if (t0) atomicAdd(&a.st->nn_events, (unsigned long long)t0);
+        if (t1) atomicAdd(&a.st->coulomb_pairs, (unsigned long long)t1);
+    }
+}
+
+// one wavefront (block of 64) per listed big cell
+template <typename T>
+__global__ __launch_bounds__(64) void k_pair_big(PairArgs<T> a) {
+    __shared__ uint64_t kk[kBigCell];
+    __shared__ uint32_t ee[kBigCell];
+    const int lane = threadIdx.x;
+    int cnt[2] = {0, 0};
+    const int64_t nbig = (int64_t)a.st->n_big;
+    for (int64_t b = blockIdx.x; b < nbig; b += gridDim.x) {
+        const uint32_t c = a.big[b];
+        const uint32_t o0 = a.off[c];
+        const int n = (int)(a.off[c + 1] - o0);
+        if (n > kBigCell) continue;  // reported by the collision pass
+        int P = 1;
+        while (P < n) P <<= 1;
+        for (int t = lane; t < P; t += 64) {
+            if (t < n) {
+                const uint2 be = a.bins[o0 + t];
+                kk[t] = ((uint64_t)(be.x >> 30) << 32) | be.y;
+                ee[t] = be.x;
+            } else {
+                kk[t] = ~0ull;
+                ee[t] = 0;
+            }
+        }
+        __syncthreads();
+        for (int k = 2; k <= P; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int t = lane; t < P; t += 64) {
+                    const int u = t ^ j;
+                    if (u > t) {
+                        const bool up = (t & k) == 0;
+                        const uint64_t x = kk[t], y = kk[u];
+                        if ((x > y) == up) {
+                            kk[t] = y;
+                            kk[u] = x;
+                            const uint32_t ex = ee[t];
+                            ee[t] = ee[u];
+                            ee[u] = ex;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        pair_classes(
+            a, c, [&](int t) { return kk[t]; }, [&](int t) { return ee[t]; }, n, lane, 64,
+            [] { __syncthreads(); }, cnt);
+        __syncthreads();
+    }
+    const int t0 = wave_sum(cnt[0]), t1 = wave_sum(cnt[1]);
+    if (lane == 0) {
+        if (t0) atomicAdd(&a.st->nn_events, (unsigned long long)t0);
+        if (t1) atomicAdd(&a.st->coulomb_pairs, (unsigned long long)t1);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Merging of superparticles (Sec. 2.3.2, the centre-of-mass merge of two
 // superparticles of one type). The paper does not say which pairs merge:
 // per cell and species, the superparticles binned by this step's push that
@@ -1665,6 +1942,29 @@ static hipError_t collide_t(pic_ctx* c, bool record) {
             hipLaunchKernelGGL(k_splits_clear<T>, dim3(grid_for(c->buf.cap[s])), dim3(kBlock), 0, c->stream, sa, s);
         hipLaunchKernelGGL(k_splits_finish, dim3(1), dim3(1), 0, c->stream, c->st, c->buf.cap[0], c->buf.cap[1],
                            c->buf.cap[2]);
+    }
+    if (cf.same_species) {
+        PairArgs<T> pa;
+        for (int s = 0; s < 3; ++s) pa.sp[s] = species<T>(c, s);
+        pa.g = g;
+        pa.off = c->off;
+        pa.bins = c->bins;
+        pa.big = c->big;
+        pa.nflag = c->nflag;
+        pa.st = c->st;
+        pa.step = (uint32_t)c->step;
+        pa.seed = cf.seed;
+        pa.h = cf.h;
+        pa.dt = cf.dt;
+        pa.m_ion = cf.m_ion;
+        pa.sigma_nn = cf.sigma_nn;
+        pa.coulomb_log = cf.coulomb_log;
+        pa.nn = (cf.same_species & 1) ? 1 : 0;
+        pa.coul = (cf.same_species & 2) ? 1 : 0;
+        pa.nc = g.nkeys;
+        hipLaunchKernelGGL(k_pair_small<T>, dim3(side ? std::min(grid_for(g.nkeys), 1024u) : grid_for(g.nkeys)),
+                           dim3(kBlock), 0, c->stream, pa);
+        hipLaunchKernelGGL(k_pair_big<T>, dim3(256), dim3(64), 0, c->stream, pa);
     }
     if (merge_step(c)) {
         MergeArgs<T> ma;

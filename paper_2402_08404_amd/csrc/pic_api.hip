@@ -114,6 +114,10 @@ const char* check_config(const pic_config* cfg) {
     if (cfg->merge_every < 0) return "merge_every must be >= 0";
     if (cfg->merge_every > 0 && !cfg->weighted) return "merging needs weighted = 1";
     if (cfg->merge_every > 0 && cfg->merge_max < 1) return "merging needs merge_max >= 1";
+    if (cfg->same_species < 0 || cfg->same_species > 3) return "same_species must be 0 .. 3";
+    if (cfg->same_species && cfg->weighted) return "same-species and Coulomb pairing need weighted = 0";
+    if ((cfg->same_species & 1) && !(cfg->sigma_nn >= 0.0)) return "sigma_nn must be >= 0";
+    if ((cfg->same_species & 2) && !(cfg->coulomb_log > 0.0)) return "coulomb_log must be > 0";
     return nullptr;
 }
 
@@ -691,6 +695,8 @@ pic_status pic_moments(pic_ctx* c, pic_moments_t* out) {
     out->splits = (int64_t)h->splits;
     out->evap_atoms = (int64_t)h->evap_atoms;
     for (int s = 0; s < 3; ++s) out->merges[s] = (int64_t)h->merges[s];
+    out->nn_events = (int64_t)h->nn_events;
+    out->coulomb_pairs = (int64_t)h->coulomb_pairs;
     return s;
 }
 

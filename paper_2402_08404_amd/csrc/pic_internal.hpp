@@ -33,6 +33,10 @@ constexpr uint32_t kTagMcc1 = 1, kTagMcc2 = 2, kTagPair1 = 3, kTagPair2 = 4, kTa
 // added to a tag for the draws of the second and later sub-particles of a
 // weighted superparticle (sub-particle q >= 1 draws with counter word q)
 constexpr uint32_t kTagSub = 16;
+// same-species and Coulomb pairing: cell shifts (Cu-Cu, e-e, Cu+-Cu+, e-Cu+)
+// and pair draws (Cu-Cu, same-species Coulomb, e-Cu+ Coulomb)
+constexpr uint32_t kTagPairNN = 8, kTagNN = 9, kTagPairEE = 10, kTagPairII = 11, kTagPairEI = 12, kTagCoul = 13,
+                   kTagCoulEI = 14;
 
 // Device-resident counters and scalars of one context.
 struct DevState {
@@ -72,6 +76,8 @@ struct DevState {
     unsigned long long splits;         // cumulative split-offs
     unsigned long long evap_atoms;     // cumulative evaporated atoms
     unsigned long long merges[3];      // cumulative merged pairs per species
+    unsigned long long nn_events;      // cumulative Cu-Cu elastic collisions
+    unsigned long long coulomb_pairs;  // cumulative Coulomb scatterings
 };
 
 // Cells are numbered tile-major: tiles of kTile^3 cells, tile index

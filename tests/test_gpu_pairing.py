@@ -1,0 +1,123 @@
+"""GPU parity of same-species and Coulomb pairing (Table colls: Cu + Cu
+elastic, Takizuka-Abe Coulomb collisions of e-e, Cu+-Cu+ and e-Cu+ pairs)
+against the FP64 oracle: the same collisions and scatterings, and the same
+velocities, for cells handled by one thread and cells handled by a
+wavefront, alone and together with the collisions and field ionization of
+the step, and over whole steps."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle
+from paper_2402_08404_amd import workloads as W
+
+from gpu_common import compare_states, dense_load, event_sets, round_load
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2402_08404_amd import pic  # noqa: E402
+
+F64, F32 = pic.PIC_F64, pic.PIC_F32
+ALL = oracle.COLL_ALL | oracle.COLL_NN | oracle.COLL_COUL
+
+
+def _pair(cfg, load, precision):
+    load = round_load(load, precision)
+    n = [len(load[s]["x"]) if s in load else 0 for s in W.SPECIES]
+    caps = (4 * n[0] + 4 * n[2] + 4096, 4 * n[1] + 2 * n[2] + 1024, n[2] + 1024)
+    g = pic.Simulation(cfg, caps=caps, precision=precision)
+    g.load(load)
+    o = oracle.Oracle(cfg)
+    o.load(load)
+    return g, o
+
+
+@pytest.mark.parametrize("precision,big", [(F64, False), (F32, False), (F64, True), (F32, True)])
+def test_pairing_parity(precision, big):
+    """Pairing alone (no cross sections of the plain method, no field):
+    cells of a few particles per species, or cells of 25-30 per species (the
+    wavefront path)."""
+    cfg = W.tiny()
+    cfg.xs_el, cfg.xs_iz, cfg.xs_cx = W.constant_tables(0.0, 0.0, 0.0)
+    cfg.same_species, cfg.sigma_nn, cfg.coulomb_log = 3, 3e-16, 10.0
+    load = dense_load(cfg, ncell=40, per=(30, 25, 28), seed=41) if big else \
+        dense_load(cfg, ncell=600, per=(5, 3, 4), seed=41)
+    g, o = _pair(cfg, load, precision)
+    g.set_phi(np.zeros(cfg.nx * cfg.ny * cfg.nz))
+    o.set_phi(np.zeros(cfg.nx * cfg.ny * cfg.nz))
+    g.step(1, pic.STEP_DEPOSIT | pic.STEP_COLLIDE)
+    o.collide(ALL)
+    m = g.moments()
+    print("Cu-Cu", m["nn_events"], o.nn_events, "Coulomb", m["coulomb_pairs"], o.coulomb_pairs, flush=True)
+    assert m["nn_events"] == o.nn_events > 20
+    assert m["coulomb_pairs"] == o.coulomb_pairs > 500
+    tol = 1e-11 if precision == F64 else 2.0 ** -19
+    compare_states(cfg, g.state(), o.state(), 0.0, tol)
+
+
+@pytest.mark.parametrize("precision", [F64, F32])
+def test_pairing_after_collisions(precision):
+    """Pairing in a collide phase that also has elastic, ionizing and
+    charge-exchange collisions and field ionization: neutrals with an event
+    sit out of the Cu-Cu pairs, ionization products take no part."""
+    cfg = W.tiny()
+    cfg.xs_el, cfg.xs_iz, cfg.xs_cx = W.constant_tables(4e-19, 2e-19, 3e-17)
+    cfg.same_species, cfg.sigma_nn, cfg.coulomb_log = 3, 3e-15, 10.0
+    load = dense_load(cfg, ncell=400, per=(7, 2, 6))
+    g, o = _pair(cfg, load, precision)
+    phi = W.synthetic_potential(cfg, 400.0, amp=0.3)
+    g.set_phi(phi)
+    o.set_phi(phi)
+    g.step(1, pic.STEP_DEPOSIT | pic.STEP_COLLIDE | pic.STEP_EVENTS)
+    o.collide(ALL)
+    ev_o = event_sets(o.last_events, o.last_fragile)
+    assert {k for k, _, _ in ev_o} >= {1, 2, 3, 4}
+    assert event_sets(g.events(), o.last_fragile) == ev_o
+    m = g.moments()
+    assert m["nn_events"] == o.nn_events > 100 and m["coulomb_pairs"] == o.coulomb_pairs > 1000
+    if not o.last_fragile:
+        # FP64: a particle may take several scatterings in sequence, each
+        # through log, cos and sincos of the device and host libraries (a few
+        # ulp apart), so 1e-11 rather than the 1e-12 of a single collision
+        tol = 1e-11 if precision == F64 else 2.0 ** -19
+        compare_states(cfg, g.state(), o.state(), 0.0, tol)
+
+
+def test_pairing_full_steps_fp64():
+    """Six whole FP64 steps of the tiny workload with Cu-Cu elastic and
+    Coulomb pairing on: events, ids and node charge bit-exact, velocities and
+    positions to rounding, the same pairing counts."""
+    cfg = W.tiny()
+    cfg.same_species, cfg.sigma_nn, cfg.coulomb_log = 3, 1e-13, 10.0   # a Cu-Cu collision every few steps
+    load = W.initial_load(cfg)
+    g = pic.Simulation(cfg, caps=(80000, 8000, 8000), precision=F64, step_rtol=1e-12)
+    g.load(load)
+    o = oracle.Oracle(cfg)
+    o.load(load)
+    g.step(1, pic.STEP_DEPOSIT)
+    g.solve(rtol=1e-12)
+    o.deposit()
+    o.solve(rtol=1e-12)
+    for s in range(6):
+        g.step(1, pic.STEP_FULL | pic.STEP_EVENTS)
+        o.step(rtol=1e-12)
+        if o.last_fragile:
+            pytest.skip("fragile decision met at step %d" % s)
+        assert event_sets(g.events(), set()) == event_sets(o.last_events, set())
+        mg, mo = g.moments(), o.moments()
+        assert mg["nn_events"] == mo["nn_events"] and mg["coulomb_pairs"] == mo["coulomb_pairs"]
+        compare_states(cfg, g.state(), o.state(), 1e-11, 1e-9)
+        assert np.array_equal(g.grid("rho"), o.Q)
+    print("Cu-Cu", mo["nn_events"], "Coulomb", mo["coulomb_pairs"], flush=True)
+    assert mo["coulomb_pairs"] > 1000 and mo["nn_events"] > 100
+
+
+def test_pairing_rejects_weighted_runs():
+    cfg = W.tiny()
+    cfg.same_species = 2
+    with pytest.raises(RuntimeError):
+        pic.Simulation(cfg, caps=(1024, 1024, 1024), weighted=True)
