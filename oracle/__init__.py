@@ -26,7 +26,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 SP_E, SP_ION, SP_NEU = 0, 1, 2
 FREE, DIR0, DIRV = 0, 1, 2
-COLL_MCC1, COLL_MCC2, COLL_FI, COLL_NN, COLL_COUL = 1, 2, 4, 8, 16
+COLL_MCC1, COLL_MCC2, COLL_FI, COLL_NN, COLL_COUL, COLL_REC = 1, 2, 4, 8, 16, 32
 COLL_ALL = 7
 ALIVE, CATHODE, ANODE, LATERAL, TIP = 0, 1, 2, 3, 4
 KIND_ELASTIC, KIND_IONIZE, KIND_CX, KIND_FI = 1, 2, 3, 4
@@ -51,7 +51,8 @@ class _Config(C.Structure):
                 ("xs_el", C.POINTER(C.c_double)), ("xs_iz", C.POINTER(C.c_double)),
                 ("xs_cx", C.POINTER(C.c_double)), ("seed", C.c_uint64),
                 ("fn_rings", C.c_int32), ("fn_az", C.c_int32), ("w_max", C.c_int32), ("pad", C.c_int32),
-                ("n_max", C.c_double), ("sigma_nn", C.c_double), ("coulomb_log", C.c_double)]
+                ("n_max", C.c_double), ("sigma_nn", C.c_double), ("coulomb_log", C.c_double),
+                ("sigma_rec", C.c_double)]
 
 
 class _Species(C.Structure):
@@ -69,7 +70,7 @@ class _CollideOut(C.Structure):
     _fields_ = [("ev", C.POINTER(_Event)), ("ev_cap", C.c_int64), ("n_ev", C.c_int64),
                 ("fragile", C.POINTER(C.c_uint32)), ("fr_cap", C.c_int64), ("n_fragile", C.c_int64),
                 ("n_kind", C.c_int64 * 5), ("n_bsi_skip", C.c_int64), ("n_kind_w", C.c_int64 * 5),
-                ("n_split", C.c_int64), ("n_nn", C.c_int64), ("n_coul", C.c_int64)]
+                ("n_split", C.c_int64), ("n_nn", C.c_int64), ("n_coul", C.c_int64), ("n_rec", C.c_int64)]
 
 
 _lib = None
@@ -173,7 +174,8 @@ def make_config(cfg) -> tuple[_Config, list]:
                 xs_el=keep[0].ctypes.data_as(dpp), xs_iz=keep[1].ctypes.data_as(dpp),
                 xs_cx=keep[2].ctypes.data_as(dpp), seed=cfg.seed, fn_rings=cfg.fn_rings, fn_az=cfg.fn_az,
                 w_max=int(getattr(cfg, "w_max", 1)), n_max=float(getattr(cfg, "n_max", 1e24)),
-                sigma_nn=float(getattr(cfg, "sigma_nn", 0.0)), coulomb_log=float(getattr(cfg, "coulomb_log", 10.0)))
+                sigma_nn=float(getattr(cfg, "sigma_nn", 0.0)), coulomb_log=float(getattr(cfg, "coulomb_log", 10.0)),
+                sigma_rec=float(getattr(cfg, "sigma_rec", 0.0)))
     return c, keep
 
 
@@ -300,6 +302,7 @@ class Oracle:
         self.merges = np.zeros(3, np.int64)      # merged pairs per species
         self.nn_events = 0                        # Cu-Cu elastic collisions
         self.coulomb_pairs = 0                    # Coulomb scatterings
+        self.recombinations = 0                   # Cu+ + e -> Cu
         self.last_events = []
         self.last_fragile = set()
         self.last_solve = (0, 0.0)
@@ -457,14 +460,14 @@ class Oracle:
         self.V_gap = self.V_gap + cfg.dt / cfg.circuit_C * (self.i_tot - i_gap)
 
     def collide(self, flags: int = COLL_ALL):
-        if flags & (COLL_NN | COLL_COUL) and any((st.w[: st.n] != 1).any() for st in self.sp):
+        if flags & (COLL_NN | COLL_COUL | COLL_REC) and any((st.w[: st.n] != 1).any() for st in self.sp):
             raise ValueError("same-species and Coulomb pairing are defined for unweighted particles")
         n_neu = self.sp[SP_NEU].n
         # room for the products (one ion and one electron per neutral) and for
         # a split-off superparticle of every particle
         for s in (SP_E, SP_ION):
             self.sp[s].ensure(n_neu + self.sp[s].n + 1)
-        self.sp[SP_NEU].ensure(n_neu + 1)
+        self.sp[SP_NEU].ensure(n_neu + self.sp[SP_ION].n + 1)
         cap = 2 * (n_neu + self.sp[SP_E].n + self.sp[SP_ION].n) + 16
         ev = (_Event * cap)()
         fr = np.zeros(cap, np.uint32)
@@ -485,6 +488,7 @@ class Oracle:
         self.splits += int(out.n_split)
         self.nn_events += int(out.n_nn)
         self.coulomb_pairs += int(out.n_coul)
+        self.recombinations += int(out.n_rec)
         self.bsi_skips += int(out.n_bsi_skip)
         return self.last_events
 
@@ -543,9 +547,10 @@ class Oracle:
 
     def step_flags(self) -> int:
         """Collision flags of a whole step: the three classes of the plain
-        method, plus Cu-Cu elastic (same_species bit 1) and Coulomb (bit 2)."""
+        method, plus Cu-Cu elastic (same_species bit 1), Coulomb (bit 2) and
+        recombination (bit 4)."""
         ss = int(getattr(self.cfg, "same_species", 0))
-        return COLL_ALL | (COLL_NN if ss & 1 else 0) | (COLL_COUL if ss & 2 else 0)
+        return COLL_ALL | (COLL_NN if ss & 1 else 0) | (COLL_COUL if ss & 2 else 0) | (COLL_REC if ss & 4 else 0)
 
     def step(self, rtol: float = 1e-8, inject: bool = True, collide_flags: int | None = None,
              solve: bool = True):
@@ -578,7 +583,8 @@ class Oracle:
                 "evaporated": self.evaporated, "evap_atoms": self.evap_atoms, "evap_expected": self.evap_expected,
                 "n_phys": np.array([int(st.w[: st.n].sum()) for st in self.sp], np.int64),
                 "events_w": self.events_w.copy(), "splits": self.splits, "merges": self.merges.copy(),
-                "nn_events": self.nn_events, "coulomb_pairs": self.coulomb_pairs}
+                "nn_events": self.nn_events, "coulomb_pairs": self.coulomb_pairs,
+                "recombinations": self.recombinations}
 
     # -- helpers for tests ----------------------------------------------------
     def gather(self, E: np.ndarray, X, Y, Z) -> np.ndarray:

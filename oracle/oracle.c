@@ -1009,10 +1009,80 @@ static int64_t coulomb_e_ion(const orc_config* c, uint32_t step, const entry* en
     return count;
 }
 
+/* Recombination Cu+ + e -> Cu (Table colls; the cited cross sections are not
+ * given, so a constant sigma_rec stands in). Readings: electrons and ions of
+ * a cell (present before this step's collisions) are paired like the
+ * collision classes above -- the fewer species (tie: the ions) as
+ * projectiles in ascending id order, targets in ascending id order shifted
+ * by floor(U_c N_t) -- and a pair recombines when U1 < P = 1 - exp(-u n
+ * sigma_rec dt), n = N_t / h^3; earlier events of the step do not exclude a
+ * particle. The atom takes the ion's position and the pair's centre-of-mass
+ * velocity (momentum conserved; the binding energy and the kinetic energy of
+ * the relative motion leave the system). */
+#define TAG_PAIR_REC 32u
+#define TAG_REC 33u
+
+typedef struct recomb { uint32_t ion_id; int64_t iidx, eidx; double v[3]; } recomb;
+
+static int recomb_cmp(const void* a, const void* b) {
+    const recomb* x = a; const recomb* y = b;
+    return x->ion_id < y->ion_id ? -1 : (x->ion_id > y->ion_id ? 1 : 0);
+}
+
+static int64_t recombine(const orc_config* c, uint32_t step, const entry* ent, int64_t ne, orc_species* sp,
+                         recomb* rec) {
+    double vol = c->h * c->h * c->h, h = c->h, dt = c->dt;
+    orc_species* El = &sp[ORC_SP_E]; orc_species* I = &sp[ORC_SP_ION];
+    int64_t nrec = 0, s0 = 0;
+    while (s0 < ne) {
+        int64_t s1 = s0;
+        while (s1 < ne && ent[s1].cell == ent[s0].cell) ++s1;
+        int64_t e0 = s0;
+        while (e0 < s1 && ent[e0].sp != ORC_SP_E) ++e0;
+        int64_t e1 = e0;
+        while (e1 < s1 && ent[e1].sp == ORC_SP_E) ++e1;
+        int64_t i0 = s0;
+        while (i0 < s1 && ent[i0].sp != ORC_SP_ION) ++i0;
+        int64_t i1 = i0;
+        while (i1 < s1 && ent[i1].sp == ORC_SP_ION) ++i1;
+        int64_t NE = e1 - e0, NI = i1 - i0;
+        if (NE > 0 && NI > 0) {
+            int ion_proj = NI <= NE;
+            int64_t P0 = ion_proj ? i0 : e0, NP = ion_proj ? NI : NE;
+            int64_t T0 = ion_proj ? e0 : i0, NT = ion_proj ? NE : NI;
+            double uc, unused;
+            draw2(c, (uint32_t)ent[s0].cell, step, TAG_PAIR_REC, 0, &uc, &unused);
+            int64_t rs = (int64_t)floor(uc * (double)NT);
+            if (rs > NT - 1) rs = NT - 1;
+            double n = (double)NT / vol;
+            for (int64_t i = 0; i < NP; ++i) {
+                const entry* pj = &ent[P0 + i];
+                const entry* tg = &ent[T0 + (rs + i) % NT];
+                int64_t ii = ion_proj ? pj->idx : tg->idx, ie = ion_proj ? tg->idx : pj->idx;
+                double u[3] = {(El->vx[ie] - I->vx[ii]) * h / dt, (El->vy[ie] - I->vy[ii]) * h / dt,
+                               (El->vz[ie] - I->vz[ii]) * h / dt};
+                double um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+                double P = -expm1(-um * n * c->sigma_rec * dt);
+                double U1, unused2;
+                draw2(c, pj->id, step, TAG_REC, 0, &U1, &unused2);
+                if (!(U1 < P)) continue;
+                recomb* r = &rec[nrec++];
+                r->ion_id = I->id[ii]; r->iidx = ii; r->eidx = ie;
+                double mt = M_EL + c->m_ion;
+                r->v[0] = (M_EL * El->vx[ie] + c->m_ion * I->vx[ii]) / mt;
+                r->v[1] = (M_EL * El->vy[ie] + c->m_ion * I->vy[ii]) / mt;
+                r->v[2] = (M_EL * El->vz[ie] + c->m_ion * I->vz[ii]) / mt;
+            }
+        }
+        s0 = s1;
+    }
+    return nrec;
+}
+
 /* Collisions of one step on the post-push state: (e,Cu) pairs, then (Cu+,Cu)
  * pairs, then field ionization of every neutral without an event, then (with
- * their flags) Cu-Cu elastic pairs, e-e, Cu+-Cu+ and e-Cu+ Coulomb pairs,
- * then the products. Ionization products (impact and field) are created in the order
+ * their flags) Cu-Cu elastic pairs, e-e, Cu+-Cu+ and e-Cu+ Coulomb pairs and
+ * recombination, then the products. Ionization products (impact and field) are created in the order
  * (impact before field, ascending neutral id), each taking two new ids: the ion
  * first, then the electron; each carries the N_coll ionized units, which the
  * neutral loses. Then the split-off superparticles, in the order (species,
@@ -1088,6 +1158,10 @@ int orc_collide(const orc_config* c, uint32_t step, int32_t flags, const double*
         o->n_coul += pair_same(c, step, 2, ent, ne, sp, used);
         o->n_coul += coulomb_e_ion(c, step, ent, ne, sp);
     }
+    recomb* rec = malloc((ne + 1) * sizeof(recomb));
+    int64_t nrec = (flags & ORC_COLL_REC) ? recombine(c, step, ent, ne, sp, rec) : 0;
+    qsort(rec, nrec, sizeof(recomb), recomb_cmp);
+    o->n_rec = nrec;
 
     int rc = 0;
     qsort(prod, nprod, sizeof(product), product_cmp);
@@ -1096,9 +1170,9 @@ int orc_collide(const orc_config* c, uint32_t step, int32_t flags, const double*
     int64_t nsp_new[3] = {0, 0, 0};
     for (int64_t k = 0; k < nspl; ++k) nsp_new[spl[k].sp]++;
     if (!grow_ok(I, nprod + nsp_new[ORC_SP_ION]) || !grow_ok(El, nprod + nsp_new[ORC_SP_E]) ||
-        !grow_ok(N, nsp_new[ORC_SP_NEU]))
+        !grow_ok(N, nsp_new[ORC_SP_NEU] + nrec))
         rc = -1;
-    uint8_t* dead = calloc(N->n + nsp_new[ORC_SP_NEU] + 1, 1);
+    uint8_t* dead = calloc(N->n + nsp_new[ORC_SP_NEU] + nrec + 1, 1);
     for (int64_t k = 0; k < nprod && rc == 0; ++k) {
         product* pr = &prod[k];
         int64_t ni = pr->nidx;
@@ -1129,6 +1203,35 @@ int orc_collide(const orc_config* c, uint32_t step, int32_t flags, const double*
         S->w[q->pidx] -= q->c;
     }
     o->n_split = nspl;
+    /* recombination products in ascending ion id, after the other products;
+     * the electron and the ion are removed */
+    uint8_t* dead_e = calloc(El->n + 1, 1);
+    uint8_t* dead_i = calloc(I->n + 1, 1);
+    for (int64_t k = 0; k < nrec && rc == 0; ++k) {
+        recomb* r = &rec[k];
+        int64_t a = N->n++;
+        N->x[a] = I->x[r->iidx]; N->y[a] = I->y[r->iidx]; N->z[a] = I->z[r->iidx];
+        N->vx[a] = r->v[0]; N->vy[a] = r->v[1]; N->vz[a] = r->v[2];
+        N->id[a] = (*next_id)++;
+        if (N->w) N->w[a] = 1;
+        dead_e[r->eidx] = 1;
+        dead_i[r->iidx] = 1;
+    }
+    for (int pass = 0; pass < 2 && nrec > 0; ++pass) {
+        orc_species* S = pass == 0 ? El : I;
+        uint8_t* dd = pass == 0 ? dead_e : dead_i;
+        int64_t w = 0;
+        for (int64_t p = 0; p < S->n; ++p) {
+            if (dd[p]) continue;
+            S->x[w] = S->x[p]; S->y[w] = S->y[p]; S->z[w] = S->z[p];
+            S->vx[w] = S->vx[p]; S->vy[w] = S->vy[p]; S->vz[w] = S->vz[p];
+            S->id[w] = S->id[p];
+            if (S->w) S->w[w] = S->w[p];
+            ++w;
+        }
+        S->n = w;
+    }
+    free(dead_e); free(dead_i); free(rec);
     /* remove the neutrals left without weight, keeping the order of the others */
     int64_t w = 0;
     for (int64_t p = 0; p < N->n; ++p) {

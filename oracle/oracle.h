@@ -39,6 +39,7 @@ typedef struct orc_config {
     double n_max;        /* SP number density [1/m^3] above which evaporated neutrals get heavier */
     double sigma_nn;     /* Cu-Cu elastic (hard-sphere) cross section [m^2] */
     double coulomb_log;  /* Coulomb logarithm ln(Lambda) of the Takizuka-Abe collisions */
+    double sigma_rec;    /* Cu+ + e -> Cu recombination cross section [m^2] */
 } orc_config;
 
 /* Superparticle weights (Sec. 2.3.2): w[p] physical particles per SP, in
@@ -66,12 +67,13 @@ typedef struct orc_collide_out {
     int64_t n_split;        /* superparticles split off by partial collisions */
     int64_t n_nn;           /* Cu-Cu elastic collisions */
     int64_t n_coul;         /* Coulomb scatterings (pairs with u > 0) */
+    int64_t n_rec;          /* recombinations */
 } orc_collide_out;
 
 enum { ORC_SP_E = 0, ORC_SP_ION = 1, ORC_SP_NEU = 2 };
 enum { ORC_ALIVE = 0, ORC_CATHODE = 1, ORC_ANODE = 2, ORC_LATERAL = 3, ORC_TIP = 4 };
 enum { ORC_FREE = 0, ORC_DIR0 = 1, ORC_DIRV = 2 };
-enum { ORC_COLL_MCC1 = 1, ORC_COLL_MCC2 = 2, ORC_COLL_FI = 4, ORC_COLL_NN = 8, ORC_COLL_COUL = 16 };
+enum { ORC_COLL_MCC1 = 1, ORC_COLL_MCC2 = 2, ORC_COLL_FI = 4, ORC_COLL_NN = 8, ORC_COLL_COUL = 16, ORC_COLL_REC = 32 };
 
 void orc_constants(double out[8]);
 void orc_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);

@@ -61,9 +61,10 @@ class Config:
     n_max: float = 1e24      # SP number density above which evaporated neutrals get heavier [1/m^3] (1e-6 per A^3)
     merge_every: int = 0     # merging of superparticles every this many steps (0: never)
     merge_max: int = 0       # superparticles of one species per cell above which pairs of them merge
-    same_species: int = 0    # bit 1: Cu-Cu elastic pairs, bit 2: Coulomb (Takizuka-Abe) pairs of charged particles
+    same_species: int = 0    # bit 1: Cu-Cu elastic, bit 2: Coulomb (Takizuka-Abe), bit 4: Cu+ + e -> Cu recombination
     sigma_nn: float = 0.0    # Cu-Cu elastic (hard-sphere) cross section [m^2]
     coulomb_log: float = 10.0  # Coulomb logarithm ln(Lambda)
+    sigma_rec: float = 0.0   # recombination cross section [m^2]
 
     @property
     def n_nodes(self) -> int:

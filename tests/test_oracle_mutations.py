@@ -97,6 +97,11 @@ MUTATIONS = [
      "for (int64_t j = 0; j < N; ++j) q[j] = ent[a0 + j].idx;", PR.pin_pairing_enumerated),
     ("e-Cu+ Coulomb with the larger density",
      "double n_l = (double)NF / vol;", "double n_l = (double)NM / vol;", PR.pin_coulomb_e_ion),
+    ("recombination probability without the density",
+     "double P = -expm1(-um * n * c->sigma_rec * dt);", "double P = -expm1(-um * c->sigma_rec * dt);",
+     PR.pin_recombination),
+    ("recombined atom with the ion's velocity",
+     "r->v[0] = (M_EL * El->vx[ie] + c->m_ion * I->vx[ii]) / mt;", "r->v[0] = I->vx[ii];", PR.pin_recombination),
 ]
 
 

@@ -13,7 +13,11 @@ from its definition rather than from the oracle's code:
 - the pairing: ascending ids rotated by floor(U_c N) with U_c from Philox
   (cell, step, tag), consecutive pairs, the last one out for odd N (Cu-Cu),
   the first three in a triangle for odd N (Coulomb), every particle of the
-  more numerous species in one e-Cu+ pair.
+  more numerous species in one e-Cu+ pair;
+- recombination Cu+ + e -> Cu: pairs at a known relative speed recombine at
+  the rate 1 - exp(-u n sigma dt); the atom appears at the ion's position
+  with the pair's centre-of-mass velocity and a new id, in ascending order
+  of the ion ids; the electron and the ion are gone.
 """
 import math
 
@@ -253,3 +257,47 @@ def test_weighted_particles_rejected():
                   "w": [2, 1]}})
     with pytest.raises(ValueError):
         o.collide(oracle.COLL_COUL)
+
+
+def pin_recombination():
+    cfg = _cfg(seed=36)
+    cfg.sigma_rec = 5e-18                         # P = 0.27 at u = 1e7 m/s
+    rng = np.random.default_rng(36)
+    ncell, u = 5000, 1e7
+    cells = _cells(cfg, ncell, rng)
+    c = np.array(cells, float)
+    d = rng.standard_normal((ncell, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    ve = d * u * cfg.dt / cfg.h
+    vi = rng.normal(0, 1e-4, (ncell, 3))
+    load = {"e": {"x": c[:, 0] + 0.3, "y": c[:, 1] + 0.5, "z": c[:, 2] + 0.5, "vx": ve[:, 0], "vy": ve[:, 1],
+                  "vz": ve[:, 2]},
+            "ion": {"x": c[:, 0] + 0.6, "y": c[:, 1] + 0.4, "z": c[:, 2] + 0.7, "vx": vi[:, 0], "vy": vi[:, 1],
+                    "vz": vi[:, 2]}}
+    o = oracle.Oracle(cfg, laplace=False)
+    o.load(load)
+    next0 = o.next_id
+    o.collide(oracle.COLL_REC)
+    st = o.state()
+    k = o.recombinations
+    urel = np.linalg.norm(ve - vi, axis=1) * cfg.h / cfg.dt
+    P = 1.0 - np.exp(-urel * (1.0 / cfg.h ** 3) * cfg.sigma_rec * cfg.dt)
+    assert abs(k - P.sum()) < 3.5 * math.sqrt((P * (1 - P)).sum()), (k, P.sum())
+    gone_e = sorted(set(range(ncell)) - set(int(i) for i in st[0]["id"]))
+    gone_i = sorted(set(range(ncell, 2 * ncell)) - set(int(i) for i in st[1]["id"]))
+    assert len(gone_e) == len(gone_i) == k > 500
+    # one electron and one ion per cell: the pair of cell j is (j, ncell + j)
+    assert [g - ncell for g in gone_i] == gone_e
+    nn = st[2]
+    assert list(nn["id"]) == list(range(next0, next0 + k))
+    j = np.array(gone_e)
+    mt = sc.m_e + cfg.m_ion
+    for key, col in (("vx", 0), ("vy", 1), ("vz", 2)):
+        want = (sc.m_e * ve[j, col] + cfg.m_ion * vi[j, col]) / mt
+        np.testing.assert_allclose(nn[key], want, rtol=1e-12, atol=1e-18)
+    for key in ("x", "y", "z"):
+        np.testing.assert_array_equal(nn[key], load["ion"][key][j])
+
+
+def test_recombination():
+    pin_recombination()
