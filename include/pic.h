@@ -149,10 +149,17 @@ typedef struct pic_config {
      * 2 atan(delta), delta normal of variance e^4 n_L ln(Lambda) dt / (8 pi eps0^2 mu^2 u^3); odd N: the
      * first three collide pairwise with dt / 2; e-Cu+: each particle of the more numerous species meets
      * one of the other (reused cyclically), n_L the smaller density. */
-    int32_t same_species;  /* bit 0: Cu + Cu elastic, bit 1: Coulomb; 0: neither */
+    int32_t same_species;  /* bit 0: Cu + Cu elastic, bit 1: Coulomb, bit 2: recombination; 0: none */
     int32_t reserved2;
     double sigma_nn;       /* Cu-Cu elastic cross section [m^2] */
     double coulomb_log;    /* Coulomb logarithm ln(Lambda), > 0 with the Coulomb bit */
+    /* Recombination Cu+ + e -> Cu (Table colls), after the Coulomb pairs: electrons and ions of a cell
+     * paired like the collision classes (the fewer species, tie: the ions, as projectiles in id order,
+     * targets shifted by floor(U_c N_t)); a pair recombines when U < 1 - exp(-u n sigma_rec dt),
+     * n = N_t / h^3; the atom takes the ion's position, the pair's centre-of-mass velocity and a new id
+     * (ascending ion ids, after the ionization products); both charges leave the node charge. A step
+     * with recombination runs its collisions before the solve. */
+    double sigma_rec;      /* recombination cross section [m^2] */
 } pic_config;
 
 typedef struct pic_buffers {
@@ -232,6 +239,7 @@ typedef struct pic_moments_t {
     int64_t merges[3];         /* cumulative merged pairs per species */
     int64_t nn_events;         /* cumulative Cu + Cu elastic collisions */
     int64_t coulomb_pairs;     /* cumulative Coulomb scatterings (pairs with u > 0) */
+    int64_t recombinations;    /* cumulative Cu+ + e -> Cu recombinations */
 } pic_moments_t;
 
 typedef struct pic_event {

@@ -1143,6 +1143,10 @@ __global__ void k_splits(SplitArgs<T> a, int s) {
         const uint32_t id = S.id[p];
         const uint32_t wd = a.bm[s][id >> 5];
         const int64_t r = (int64_t)a.pf[s][id >> 5] + __popc(wd & ((1u << (id & 31)) - 1u));
+        if (r >= n) {  // a bit set that no split-off of the phase set
+            atomicCAS(&a.st->error, 0, PIC_E_STATE);
+            continue;
+        }
         const int64_t m = base + r;
         const uint32_t c = a.c[s][p];
         S.x[m] = S.x[p];
@@ -1464,9 +1468,17 @@ struct PairArgs {
     DevState* st;
     uint32_t step;
     uint64_t seed;
-    double h, dt, m_ion, sigma_nn, coulomb_log;
-    int nn, coul;
+    double h, dt, m_ion, sigma_nn, coulomb_log, sigma_rec;
+    int nn, coul, rec;
     int64_t nc;
+    // recombination: the charge is corrected here; the recombined ions are
+    // listed (slot), flagged in a bitmap over ids, and their atoms' velocities
+    // kept per ion slot until k_rec_place
+    int64_t* rho;
+    uint32_t* rec_list;
+    double* rec_v;
+    uint32_t* rec_bm;
+    const uint32_t* rec_pf;
 };
 
 // Eq. du: Delta u = R^-1(theta, phi) [R^-1(theta', phi') - I] (0, 0, |u|)
@@ -1556,29 +1568,36 @@ __device__ inline int pair_shift(uint64_t seed, uint32_t lcell, uint32_t step, u
 // sorted by (species, id): kv[t] = species << 32 | id, ev[t] = the value.
 // lane / lanes split the disjoint pairs (1 / 1 for one thread per cell);
 // sync() orders the rounds that reuse a particle.
-template <typename T, typename KV, typename EV, typename Sync>
-__device__ inline void pair_classes(const PairArgs<T>& a, uint32_t cell, const KV& kv, const EV& ev, int n, int lane,
-                                    int lanes, Sync sync, int cnt[2]) {
-    int b0[4] = {0, 0, 0, 0};
-    for (int t = 0; t < n; ++t) b0[(int)(kv(t) >> 32) + 1] = t + 1;
-    for (int s = 1; s < 4; ++s) b0[s] = b0[s] > b0[s - 1] ? b0[s] : b0[s - 1];
-    const uint32_t lc = linear_cell(a.g, cell);
-    const double vol = a.h * a.h * a.h;
-    const auto slot = [&](int t) { return ev(t) & 0x3FFFFFFFu; };
-    const auto idof = [&](int t) { return (uint32_t)(kv(t) & 0xFFFFFFFFu); };
-    if (a.nn) {
-        const int o = b0[PIC_NEUTRAL], N = b0[PIC_NEUTRAL + 1] - o;
-        if (N >= 2) {
-            const int sh = pair_shift(a.seed, lc, a.step, kTagPairNN, N);
-            const double n = (double)N / vol;
-            for (int j = 2 * lane; j + 1 < N; j += 2 * lanes) {
-                const int ta = o + (sh + j) % N, tb = o + (sh + j + 1) % N;
-                cnt[0] += nn_pair(a, slot(ta), idof(ta), slot(tb), idof(tb), n);
-            }
-            sync();
-        }
-    }
-    if (!a.coul) return;
+// One electron-ion pair of the recombination class; returns 1 if it
+// recombined (the electron is removed at once, the ion by k_rec_clear)
+template <typename T>
+__device__ inline int rec_pair(const PairArgs<T>& a, uint32_t pid, uint32_t ie, uint32_t ii, double n) {
+    const Species<T>& E = a.sp[PIC_ELECTRON];
+    const Species<T>& I = a.sp[PIC_ION];
+    const double s = a.h / a.dt;
+    const double vE[3] = {(double)E.vx[ie], (double)E.vy[ie], (double)E.vz[ie]};
+    const double vI[3] = {(double)I.vx[ii], (double)I.vy[ii], (double)I.vz[ii]};
+    const double u[3] = {(vE[0] - vI[0]) * s, (vE[1] - vI[1]) * s, (vE[2] - vI[2]) * s};
+    const double um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const double P = -expm1(-um * n * a.sigma_rec * a.dt);
+    if (!(draw2(a.seed, pid, a.step, kTagRec, 0).a < P)) return 0;
+    const double mt = kMe + a.m_ion;
+    for (int k = 0; k < 3; ++k) a.rec_v[3 * (int64_t)ii + k] = (kMe * vE[k] + a.m_ion * vI[k]) / mt;
+    const uint32_t idi = I.id[ii];
+    atomicOr(&a.rec_bm[idi >> 5], 1u << (idi & 31));
+    const unsigned long long q = atomicAdd(&a.st->n_rec, 1ull);
+    a.rec_list[q] = ii;
+    // the deposit of this step counted both charges
+    unsigned long long* rho = (unsigned long long*)a.rho;
+    deposit_one(a.g, rho, (double)E.x[ie], (double)E.y[ie], (double)E.z[ie], 1);
+    deposit_one(a.g, rho, (double)I.x[ii], (double)I.y[ii], (double)I.z[ii], -1);
+    E.id[ie] = kDead;
+    return 1;
+}
+
+template <typename T, typename SL, typename ID, typename Sync>
+__device__ inline void pair_coulomb(const PairArgs<T>& a, const int b0[4], uint32_t lc, double vol, const SL& slot,
+                                    const ID& idof, int lane, int lanes, Sync sync, int cnt[3]) {
     for (int sp = PIC_ELECTRON; sp <= PIC_ION; ++sp) {
         const int o = b0[sp], N = b0[sp + 1] - o;
         if (N < 2) continue;
@@ -1620,9 +1639,49 @@ __device__ inline void pair_classes(const PairArgs<T>& a, uint32_t cell, const K
     }
 }
 
+template <typename T, typename KV, typename EV, typename Sync>
+__device__ inline void pair_classes(const PairArgs<T>& a, uint32_t cell, const KV& kv, const EV& ev, int n, int lane,
+                                    int lanes, Sync sync, int cnt[3]) {
+    int b0[4] = {0, 0, 0, 0};
+    for (int t = 0; t < n; ++t) b0[(int)(kv(t) >> 32) + 1] = t + 1;
+    for (int s = 1; s < 4; ++s) b0[s] = b0[s] > b0[s - 1] ? b0[s] : b0[s - 1];
+    const uint32_t lc = linear_cell(a.g, cell);
+    const double vol = a.h * a.h * a.h;
+    const auto slot = [&](int t) { return ev(t) & 0x3FFFFFFFu; };
+    const auto idof = [&](int t) { return (uint32_t)(kv(t) & 0xFFFFFFFFu); };
+    if (a.nn) {
+        const int o = b0[PIC_NEUTRAL], N = b0[PIC_NEUTRAL + 1] - o;
+        if (N >= 2) {
+            const int sh = pair_shift(a.seed, lc, a.step, kTagPairNN, N);
+            const double n = (double)N / vol;
+            for (int j = 2 * lane; j + 1 < N; j += 2 * lanes) {
+                const int ta = o + (sh + j) % N, tb = o + (sh + j + 1) % N;
+                cnt[0] += nn_pair(a, slot(ta), idof(ta), slot(tb), idof(tb), n);
+            }
+            sync();
+        }
+    }
+    if (a.coul) pair_coulomb(a, b0, lc, vol, slot, idof, lane, lanes, sync, cnt);
+    if (a.rec) {
+        const int oe = b0[PIC_ELECTRON], NE = b0[PIC_ELECTRON + 1] - oe;
+        const int oi = b0[PIC_ION], NI = b0[PIC_ION + 1] - oi;
+        if (NE > 0 && NI > 0) {
+            const bool ion_proj = NI <= NE;
+            const int oP = ion_proj ? oi : oe, NP = ion_proj ? NI : NE, oT = ion_proj ? oe : oi, NT = ion_proj ? NE : NI;
+            const int sh = pair_shift(a.seed, lc, a.step, kTagPairRec, NT);
+            const double n = (double)NT / vol;
+            for (int i = lane; i < NP; i += lanes) {
+                const int tp = oP + i, tt = oT + (sh + i) % NT;
+                cnt[2] += rec_pair(a, idof(tp), slot(ion_proj ? tt : tp), slot(ion_proj ? tp : tt), n);
+            }
+            sync();
+        }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_pair_small(PairArgs<T> a) {
-    int cnt[2] = {0, 0};
+    int cnt[3] = {0, 0, 0};
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < a.nc; c += stride) {
         const uint32_t o0 = a.off[c];
@@ -1660,7 +1719,7 @@ __global__ __launch_bounds__(64) void k_pair_big(PairArgs<T> a) {
     __shared__ uint64_t kk[kBigCell];
     __shared__ uint32_t ee[kBigCell];
     const int lane = threadIdx.x;
-    int cnt[2] = {0, 0};
+    int cnt[3] = {0, 0, 0};
     const int64_t nbig = (int64_t)a.st->n_big;
     for (int64_t b = blockIdx.x; b < nbig; b += gridDim.x) {
         const uint32_t c = a.big[b];
@@ -1709,6 +1768,70 @@ __global__ __launch_bounds__(64) void k_pair_big(PairArgs<T> a) {
         if (t0) atomicAdd(&a.st->nn_events, (unsigned long long)t0);
         if (t1) atomicAdd(&a.st->coulomb_pairs, (unsigned long long)t1);
     }
+}
+
+// The atoms of the recombinations of the phase, in ascending order of the
+// recombined ions' ids (their ranks in the bitmap), after the other
+// products; then the ions are removed and the bits cleared.
+template <typename T>
+__global__ void k_rec_place(PairArgs<T> a) {
+    const Species<T>& I = a.sp[PIC_ION];
+    const Species<T>& N = a.sp[PIC_NEUTRAL];
+    const int64_t n = (int64_t)a.st->n_rec;
+    const int64_t base = (int64_t)a.st->n_slots[PIC_NEUTRAL];
+    if (base + n > N.cap) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && n) atomicCAS(&a.st->error, 0, PIC_E_CAPACITY);
+        return;
+    }
+    const uint32_t id0 = (uint32_t)a.st->next_id;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+        const uint32_t p = a.rec_list[q];
+        const uint32_t id = I.id[p];
+        const uint32_t wd = a.rec_bm[id >> 5];
+        const int64_t r = (int64_t)a.rec_pf[id >> 5] + __popc(wd & ((1u << (id & 31)) - 1u));
+        if (r >= n) {  // a bit set that no recombination of the phase set
+            atomicCAS(&a.st->error, 0, PIC_E_STATE);
+            continue;
+        }
+        const int64_t m = base + r;
+        N.x[m] = I.x[p];
+        N.y[m] = I.y[p];
+        N.z[m] = I.z[p];
+        N.vx[m] = (T)a.rec_v[3 * (int64_t)p + 0];
+        N.vy[m] = (T)a.rec_v[3 * (int64_t)p + 1];
+        N.vz[m] = (T)a.rec_v[3 * (int64_t)p + 2];
+        N.id[m] = id0 + (uint32_t)r;
+        if (N.w) N.w[m] = 1u;
+    }
+}
+
+template <typename T>
+__global__ void k_rec_clear(PairArgs<T> a) {
+    const Species<T>& I = a.sp[PIC_ION];
+    const int64_t n = (int64_t)a.st->n_rec;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) {
+        const uint32_t p = a.rec_list[q];
+        const uint32_t id = I.id[p];
+        atomicAnd(&a.rec_bm[id >> 5], ~(1u << (id & 31)));
+        I.id[p] = kDead;
+    }
+}
+
+__global__ void k_rec_finish(DevState* st, int64_t cap_n) {
+    const unsigned long long n = st->n_rec;
+    st->n_rec = 0;
+    if (st->n_slots[PIC_NEUTRAL] + n > (unsigned long long)cap_n) return;  // the error is set
+    st->n_slots[PIC_NEUTRAL] += n;
+    st->next_id += n;
+    st->recombinations += n;
+}
+
+__global__ void k_words_rec(const DevState* st, uint32_t* words, int64_t maxw) {
+    unsigned long long w = (st->next_id + 31ull) >> 5;
+    if (st->n_rec == 0) w = 0;
+    *words = (uint32_t)(w < (unsigned long long)maxw ? w : (unsigned long long)maxw);
 }
 
 // ---------------------------------------------------------------------------
@@ -1959,12 +2082,29 @@ static hipError_t collide_t(pic_ctx* c, bool record) {
         pa.m_ion = cf.m_ion;
         pa.sigma_nn = cf.sigma_nn;
         pa.coulomb_log = cf.coulomb_log;
+        pa.sigma_rec = cf.sigma_rec;
         pa.nn = (cf.same_species & 1) ? 1 : 0;
         pa.coul = (cf.same_species & 2) ? 1 : 0;
+        pa.rec = (cf.same_species & 4) ? 1 : 0;
         pa.nc = g.nkeys;
+        pa.rho = c->buf.rho;
+        pa.rec_list = c->rec_list;
+        pa.rec_v = c->rec_v;
+        pa.rec_bm = c->rec_bm;
+        pa.rec_pf = c->rec_pf;
         hipLaunchKernelGGL(k_pair_small<T>, dim3(side ? std::min(grid_for(g.nkeys), 1024u) : grid_for(g.nkeys)),
                            dim3(kBlock), 0, c->stream, pa);
         hipLaunchKernelGGL(k_pair_big<T>, dim3(256), dim3(64), 0, c->stream, pa);
+        if (pa.rec) {
+            uint32_t* wrec = c->dyn + 16;
+            hipLaunchKernelGGL(k_words_rec, dim3(1), dim3(1), 0, c->stream, c->st, wrec, c->bm_words);
+            e = scan_u32(c, c->rec_bm, c->rec_pf, c->bm_words, wrec, nullptr, false, true);
+            if (e != hipSuccess) return e;
+            const unsigned Gr = grid_for(c->buf.cap[1]);
+            hipLaunchKernelGGL(k_rec_place<T>, dim3(Gr), dim3(kBlock), 0, c->stream, pa);
+            hipLaunchKernelGGL(k_rec_clear<T>, dim3(Gr), dim3(kBlock), 0, c->stream, pa);
+            hipLaunchKernelGGL(k_rec_finish, dim3(1), dim3(1), 0, c->stream, c->st, c->buf.cap[2]);
+        }
     }
     if (merge_step(c)) {
         MergeArgs<T> ma;

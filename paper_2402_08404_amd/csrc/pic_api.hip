@@ -114,7 +114,8 @@ const char* check_config(const pic_config* cfg) {
     if (cfg->merge_every < 0) return "merge_every must be >= 0";
     if (cfg->merge_every > 0 && !cfg->weighted) return "merging needs weighted = 1";
     if (cfg->merge_every > 0 && cfg->merge_max < 1) return "merging needs merge_max >= 1";
-    if (cfg->same_species < 0 || cfg->same_species > 3) return "same_species must be 0 .. 3";
+    if (cfg->same_species < 0 || cfg->same_species > 7) return "same_species must be 0 .. 7";
+    if ((cfg->same_species & 4) && !(cfg->sigma_rec >= 0.0)) return "sigma_rec must be >= 0";
     if (cfg->same_species && cfg->weighted) return "same-species and Coulomb pairing need weighted = 0";
     if ((cfg->same_species & 1) && !(cfg->sigma_nn >= 0.0)) return "sigma_nn must be >= 0";
     if ((cfg->same_species & 2) && !(cfg->coulomb_log > 0.0)) return "coulomb_log must be > 0";
@@ -221,6 +222,12 @@ size_t pic::scratch_layout(pic_ctx* c, const pic_config* cfg, const int64_t cap[
     t->phi_prev = (double*)take(nn * 8);
     t->partials = (double*)take(parts * 8);
     t->mg = take(mg_bytes(cfg));
+    if (cfg->same_species & 4) {
+        t->rec_list = (uint32_t*)take(std::max<int64_t>(cap[1], 1) * 4);
+        t->rec_v = (double*)take(std::max<int64_t>(cap[1], 1) * 24);
+        t->rec_bm = (uint32_t*)take(words * 4);
+        t->rec_pf = (uint32_t*)take(words * 4);
+    }
     if (cfg->weighted) {
         t->fi_cnt = (uint32_t*)take(cap[2] * 4);
         t->prod_c = (uint32_t*)take(cap[2] * 4);
@@ -384,6 +391,7 @@ pic_status pic_init(const pic_config* cfg, const pic_buffers* bufs, void* hip_st
     H(launch_zero(c->off, ((size_t)g.nkeys + 1) * 4, c->stream), "zero");
     if (cfg->weighted)
         for (int k = 0; k < 3; ++k) H(launch_zero(c->split_bm[k], c->bm_words * 4, c->stream), "zero");
+    if (c->rec_bm) H(launch_zero(c->rec_bm, c->bm_words * 4, c->stream), "zero");
     H(launch_zero(bufs->rho, g.nn * 8, c->stream), "zero");
     H(static_work_setup(&c->static_work), "static work array");
     H(launch_node_types(c), "node types");
@@ -583,9 +591,10 @@ pic_status pic_step(pic_ctx* c, int32_t nsteps, uint32_t flags) {
         // only the charge (already deposited), the potential and the field,
         // so without profiling a step that does both runs its collisions on
         // the side stream, concurrently with the solve.
-        // A step that merges superparticles corrects the charge after its
-        // collisions, so its solve waits for them.
-        const bool side = !c->prof && (flags & PIC_STEP_COLLIDE) && (flags & PIC_STEP_SOLVE) && !merge_step(c);
+        // A step that merges superparticles, or recombines, corrects the
+        // charge after its collisions, so its solve waits for them.
+        const bool side = !c->prof && (flags & PIC_STEP_COLLIDE) && (flags & PIC_STEP_SOLVE) && !merge_step(c) &&
+                          !(c->cfg.same_species & 4);
         bool joined = true;
         if (s == PIC_OK && (flags & PIC_STEP_COLLIDE)) {
             if (!c->bins_valid) return fail(c, PIC_E_INVALID_ARG, "the collide phase needs a push or deposit phase first");
@@ -697,6 +706,7 @@ pic_status pic_moments(pic_ctx* c, pic_moments_t* out) {
     for (int s = 0; s < 3; ++s) out->merges[s] = (int64_t)h->merges[s];
     out->nn_events = (int64_t)h->nn_events;
     out->coulomb_pairs = (int64_t)h->coulomb_pairs;
+    out->recombinations = (int64_t)h->recombinations;
     return s;
 }
 

@@ -37,6 +37,8 @@ constexpr uint32_t kTagSub = 16;
 // and pair draws (Cu-Cu, same-species Coulomb, e-Cu+ Coulomb)
 constexpr uint32_t kTagPairNN = 8, kTagNN = 9, kTagPairEE = 10, kTagPairII = 11, kTagPairEI = 12, kTagCoul = 13,
                    kTagCoulEI = 14;
+// recombination: cell shift and pair draws
+constexpr uint32_t kTagPairRec = 32, kTagRec = 33;
 
 // Device-resident counters and scalars of one context.
 struct DevState {
@@ -78,6 +80,8 @@ struct DevState {
     unsigned long long merges[3];      // cumulative merged pairs per species
     unsigned long long nn_events;      // cumulative Cu-Cu elastic collisions
     unsigned long long coulomb_pairs;  // cumulative Coulomb scatterings
+    unsigned long long n_rec;          // recombinations of this collide phase
+    unsigned long long recombinations; // cumulative recombinations
 };
 
 // Cells are numbered tile-major: tiles of kTile^3 cells, tile index
@@ -426,6 +430,11 @@ struct pic_ctx {
     double* split_v[3] = {};         // per species and slot: velocity of the split-off (3 values)
     uint32_t* split_bm[3] = {};      // per species: split-off parents as a bitmap over ids
     uint32_t* split_pf[3] = {};      // their word prefix counts
+    // recombination (cfg.same_species & 4 only)
+    uint32_t* rec_list = nullptr;    // cap ion: slots of the recombined ions of the phase
+    double* rec_v = nullptr;         // cap ion: velocity of the atom (3 values)
+    uint32_t* rec_bm = nullptr;      // recombined ions as a bitmap over ids
+    uint32_t* rec_pf = nullptr;      // its word prefix counts
     bool circuit = false;            // cfg.circuit_R > 0: the anode follows the RC circuit
     double evap_flux = 0.0;          // Clausius-Clapeyron flux at cfg.surface_T [1/(m^2 s)]
     double evap_vsig = 0.0;          // sqrt(k_B T / m) dt / h

@@ -51,7 +51,8 @@ class pic_config(C.Structure):
                 ("surface_T", C.c_double), ("circuit_R", C.c_double), ("circuit_C", C.c_double),
                 ("weighted", C.c_int32), ("w_max", C.c_int32), ("n_max", C.c_double),
                 ("merge_every", C.c_int32), ("merge_max", C.c_int32), ("same_species", C.c_int32),
-                ("reserved2", C.c_int32), ("sigma_nn", C.c_double), ("coulomb_log", C.c_double)]
+                ("reserved2", C.c_int32), ("sigma_nn", C.c_double), ("coulomb_log", C.c_double),
+                ("sigma_rec", C.c_double)]
 
 
 class pic_buffers(C.Structure):
@@ -82,7 +83,7 @@ class pic_moments_t(C.Structure):
                 ("v_gap", C.c_double), ("i_gap", C.c_double), ("i_tot", C.c_double),
                 ("n_phys", C.c_int64 * 3), ("events_w", C.c_int64 * 5), ("splits", C.c_int64),
                 ("evap_atoms", C.c_int64), ("merges", C.c_int64 * 3), ("nn_events", C.c_int64),
-                ("coulomb_pairs", C.c_int64)]
+                ("coulomb_pairs", C.c_int64), ("recombinations", C.c_int64)]
 
 
 class pic_unet_config(C.Structure):
@@ -205,7 +206,8 @@ def pic_moments(ctx) -> dict:
             "evaporated": m.evaporated, "evap_expected": m.evap_expected, "bomb_energy": np.array(m.bomb_energy[:]),
             "v_gap": m.v_gap, "i_gap": m.i_gap, "i_tot": m.i_tot, "n_phys": np.array(m.n_phys[:]),
             "events_w": np.array(m.events_w[:]), "splits": m.splits, "evap_atoms": m.evap_atoms,
-            "merges": np.array(m.merges[:]), "nn_events": m.nn_events, "coulomb_pairs": m.coulomb_pairs}
+            "merges": np.array(m.merges[:]), "nn_events": m.nn_events, "coulomb_pairs": m.coulomb_pairs,
+            "recombinations": m.recombinations}
 
 
 def pic_events(ctx, cap: int) -> list:
@@ -316,7 +318,7 @@ def make_config(cfg: workloads.Config, precision=PIC_F64, solver=PIC_SOLVER_CG, 
                    w_max=int(getattr(cfg, "w_max", 1)), n_max=float(getattr(cfg, "n_max", 1e24)),
                    merge_every=int(getattr(cfg, "merge_every", 0)), merge_max=int(getattr(cfg, "merge_max", 0)),
                    same_species=int(getattr(cfg, "same_species", 0)), sigma_nn=float(getattr(cfg, "sigma_nn", 0.0)),
-                   coulomb_log=float(getattr(cfg, "coulomb_log", 10.0)))
+                   coulomb_log=float(getattr(cfg, "coulomb_log", 10.0)), sigma_rec=float(getattr(cfg, "sigma_rec", 0.0)))
     return c, keep
 
 
