@@ -1,0 +1,128 @@
+/* pic_rz.h -- C ABI of the 2D axisymmetric (r, z) 2D3V variant of the
+ * particle-mesh step (Sec. 2.2: an axisymmetric vacuum mesh around the tip,
+ * three velocity components with the azimuthal one kept, particles rotated
+ * back into the r-z plane every step, reflection at the axis, removal at the
+ * cathode, the anode and the open side, leapfrog integration).
+ *
+ * Scope: the node grid with its tip, Poisson's equation in cylindrical
+ * finite-volume form solved by FP64 conjugate gradients, the node field,
+ * the gather, push, rotation and removal of electrons, Cu+ ions and Cu
+ * neutrals, and the fixed-point charge deposit. The collision, emission and
+ * surface stages of the 3D library are not part of this variant.
+ *
+ * Discretization: nodes at (r, z) = (i h, k h), 0 <= i < nr, 0 <= k < nz,
+ * node n = k * nr + i. Nodes of the plane k = 0 and inside the tip (a
+ * cylinder of radius tip_r on the axis up to tip_h - tip_r, a hemisphere on
+ * top) are held at 0 V, k = nz - 1 at V0; the side r = (nr - 1) h has zero
+ * normal field. For a free node, with annular control volumes r in
+ * [r_i - h/2, r_i + h/2] clipped to [0, (nr - 1) h]:
+ *     sum_j c_ij (phi_i - phi_j) = Q_i / (pi eps0 h),
+ * couplings c = 2 (i - 1/2) and 2 (i + 1/2) through the radial faces (none
+ * through the axis or the side), (r_hi^2 - r_lo^2) / h^2 through each axial
+ * face. V0 = apex_field / F1 with F1 = phi1(0, tip_h + h) / h from the
+ * unit-anode solution phi1 (as in the 3D library).
+ *
+ * Particles (per species 0 electrons, 1 Cu+, 2 Cu): r, z in grid units
+ * (r / h, z / h), vr, vt, vz (radial, azimuthal, axial) in grid units per
+ * step (v dt / h), uint32 ids (0xFFFFFFFF: a free slot). One push: the kick
+ * of (vr, vz) by the bilinearly gathered node field (E_r = 0 on the axis and
+ * on the side), the drift x = r + vr, y = vt, z += vz in the particle's own
+ * Cartesian frame, then r' = sqrt(x^2 + y^2) and (vr, vt) turned by the
+ * angle atan2(y, x); removal (the slot's id set free) at z <= 0, z >=
+ * nz - 1, r' >= nr - 1 or inside the tip. Deposit: bilinear weights per axis
+ * quantized to 2^-20, every particle adds exactly 2^40 units of 2^-40 e.
+ */
+#ifndef PIC_RZ_H
+#define PIC_RZ_H
+#include <stddef.h>
+#include <stdint.h>
+
+#include "pic.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pic_rz_config {
+    int32_t nr, nz;        /* nodes along r and z, nr >= 4, nz >= 4 */
+    double h;              /* node spacing [m] */
+    double tip_r;          /* tip radius [m] (0: no tip) */
+    double tip_h;          /* total tip height to the apex [m] */
+    double apex_field;     /* Laplace field just above the apex [V/m] */
+    double dt;             /* time step [s] */
+    double m_ion;          /* Cu mass [kg] */
+    double laplace_rtol;   /* tolerance of the unit-anode solve at init */
+    int32_t maxit;         /* iteration limit of the solve inside pic_rz_step */
+    int32_t reserved;
+    double step_rtol;      /* tolerance of the solve inside pic_rz_step */
+} pic_rz_config;
+
+typedef struct pic_rz_buffers {
+    /* per species s: arrays of capacity cap[s] (device memory, FP64); the
+     * first n[s] slots hold the initial particles when pic_rz_init is called */
+    double* r[3];
+    double* z[3];
+    double* vr[3];
+    double* vt[3];
+    double* vz[3];
+    uint32_t* id[3];
+    int64_t cap[3];
+    int64_t n[3];
+    double* phi;           /* nr*nz potential [V] */
+    double* phi1;          /* nr*nz unit-anode potential, written by pic_rz_init */
+    int64_t* rho;          /* nr*nz node charge [2^-40 e] */
+    double* field;         /* 2*nr*nz node field (E_r, E_z) [V/m] */
+    uint8_t* node_type;    /* nr*nz: 0 free, 1 held at 0 V, 2 held at V0 */
+    void* scratch;         /* pic_rz_scratch_size bytes, 256-byte aligned */
+    size_t scratch_bytes;
+} pic_rz_buffers;
+
+typedef struct pic_rz_moments_t {
+    int64_t n_alive[3];      /* alive particles per species */
+    int64_t absorbed[3][5];  /* cumulative removals: 1 cathode, 2 anode, 3 side, 4 tip */
+    int64_t q_total;         /* sum of rho [2^-40 e] */
+    int64_t step;            /* step counter */
+    double v0;               /* anode potential [V] */
+    double apex_field1;      /* F1, apex field per volt of anode potential [1/m] */
+    int32_t last_cg_iters;   /* iterations of the last solve */
+    int32_t error;           /* sticky error code */
+} pic_rz_moments_t;
+
+typedef struct pic_rz_ctx pic_rz_ctx;
+
+/* flags of pic_rz_step */
+#define PIC_RZ_PUSH 1u     /* gather, push, rotation, removal */
+#define PIC_RZ_DEPOSIT 2u  /* charge deposit into rho */
+#define PIC_RZ_SOLVE 4u    /* Poisson solve to step_rtol from the previous potential, then the node field */
+#define PIC_RZ_ADVANCE 8u  /* count the step */
+#define PIC_RZ_FIELD 16u   /* without PIC_RZ_SOLVE: the node field of the current phi */
+#define PIC_RZ_FULL 15u
+
+/* Bytes of work memory for cfg and cap. Invalid config: PIC_E_INVALID_ARG. */
+pic_status pic_rz_scratch_size(const pic_rz_config* cfg, const int64_t cap[3], size_t* bytes);
+
+/* Create a context on hip_stream (NULL: the default stream): node types, the
+ * unit-anode solve (to laplace_rtol) into phi1, V0, phi = V0 phi1 and its
+ * field. Buffers are caller-owned; the context keeps their pointers.
+ * Errors: PIC_E_INVALID_ARG (config, buffers, n > cap), PIC_E_NOT_CONVERGED,
+ * PIC_E_HIP. */
+pic_status pic_rz_init(const pic_rz_config* cfg, const pic_rz_buffers* bufs, void* hip_stream, pic_rz_ctx** out);
+
+/* nsteps steps of the stages in flags, in the order push, deposit, solve. */
+pic_status pic_rz_step(pic_rz_ctx* ctx, int32_t nsteps, uint32_t flags);
+
+/* Solve for the charge in rho from the current phi until ||b - A phi|| <=
+ * rtol ||b|| (b with the held values moved to the right-hand side), then the
+ * node field. info may be NULL. PIC_E_NOT_CONVERGED if maxit is reached. */
+pic_status pic_rz_solve(pic_rz_ctx* ctx, double rtol, int32_t maxit, pic_solve_info* info);
+
+/* Synchronizes the stream and reports counts and the sticky error. */
+pic_status pic_rz_moments(pic_rz_ctx* ctx, pic_rz_moments_t* out);
+
+const char* pic_rz_last_error(const pic_rz_ctx* ctx);
+void pic_rz_destroy(pic_rz_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -15,13 +15,18 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def _declared():
-    src = open(os.path.join(ROOT, "include", "pic.h")).read()
-    return sorted(set(re.findall(r"\b(pic_[a-z_]+)\s*\(", src)))
+    names = set()
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", h)).read()
+            names |= set(re.findall(r"\b((?:pic|unet)_[a-z_]+)\s*\(", src))
+    return sorted(names)
 
 
 def test_exports_every_declared_symbol():
     names = _declared()
-    assert {"pic_init", "pic_inject", "pic_step", "pic_solve_poisson", "pic_moments", "pic_destroy"} <= set(names)
+    assert {"pic_init", "pic_inject", "pic_step", "pic_solve_poisson", "pic_moments", "pic_destroy",
+            "pic_rz_init", "pic_rz_step", "pic_rz_solve", "unet_forward"} <= set(names)
     L = pic.lib()
     for n in names:
         assert hasattr(L, n), n

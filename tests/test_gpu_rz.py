@@ -1,0 +1,132 @@
+"""GPU parity of the axisymmetric (r, z) 2D3V variant (include/pic_rz.h,
+Sec. 2.2) against the FP64 oracle of oracle/rz.py: node types bit-exact, the
+unit-anode potential and V0, the node field, one push with the rotation
+back into the r-z plane (positions and velocities per particle by id,
+removals), the fixed-point deposit bit-exact, and whole steps of push,
+deposit and solve."""
+import math
+
+import numpy as np
+import pytest
+import scipy.constants as sc
+
+torch = pytest.importorskip("torch")
+
+from oracle.rz import RZ
+
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2402_08404_amd import rz  # noqa: E402
+
+M_CU = 63.546 * sc.atomic_mass
+GEOM = dict(nr=32, nz=80, h=2e-9, tip_r=4e-9, tip_h=40e-9, apex_field=10e9, dt=5e-17, m_ion=M_CU)
+
+
+def _load(o, rng, n=(3000, 1500, 1500)):
+    out = {}
+    for s, m in enumerate(n):
+        r = rng.uniform(0.0, o.nr - 1.5, m)
+        z = rng.uniform(0.5, o.nz - 1.5, m)
+        ok = ~o.inside_tip(r, z)
+        r, z = r[ok], z[ok]
+        k = len(r)
+        sv = (0.05, 0.002, 0.001)[s]
+        out[s] = {"r": r, "z": z, "vr": rng.normal(0, sv, k), "vt": rng.normal(0, sv, k),
+                  "vz": rng.normal(0, sv, k)}
+    return out
+
+
+def _pair(seed=1, n=(3000, 1500, 1500)):
+    o = RZ(GEOM["nr"], GEOM["nz"], GEOM["h"], GEOM["tip_r"], GEOM["tip_h"], GEOM["apex_field"], GEOM["dt"],
+           GEOM["m_ion"])
+    load = _load(o, np.random.default_rng(seed), n)
+    nid = 0
+    for s in range(3):
+        m = len(load[s]["r"])
+        o.load(s, load[s], np.arange(nid, nid + m))
+        nid += m
+    g = rz.RZSimulation(**GEOM, load=load, laplace_rtol=1e-13, step_rtol=1e-14)
+    return g, o
+
+
+def _compare(g, o, tol):
+    gs = g.state()
+    for s in range(3):
+        a, b = gs[s], o.sp[s]
+        assert np.array_equal(np.sort(a["id"]), np.sort(b["id"])), s
+        if len(b["id"]) == 0:
+            continue
+        ia, ib = np.argsort(a["id"]), np.argsort(b["id"])
+        for k in ("r", "z", "vr", "vt", "vz"):
+            d = np.abs(a[k][ia] - b[k][ib])
+            scale = np.abs(b[k][ib]) + 1e-3 * np.abs(b[k]).max() + 1e-300
+            assert (d <= tol * scale).all(), (s, k, (d / scale).max())
+
+
+def test_rz_types_laplace_field():
+    g, o = _pair()
+    assert np.array_equal(g.grid("node_type"), o.type)
+    m = g.moments()
+    assert m["v0"] == pytest.approx(o.V0, rel=1e-10)
+    phi1 = g.grid("phi1")
+    assert np.abs(phi1 - o.phi1).max() <= 1e-10
+    E = g.grid("field").reshape(-1, 2)
+    assert np.abs(E - o.E).max() <= 1e-9 * np.abs(o.E).max()
+
+
+def test_rz_push_and_deposit():
+    g, o = _pair(seed=2)
+    g.set_phi(o.phi)
+    for _ in range(5):
+        g.step(1, rz.PIC_RZ_PUSH | rz.PIC_RZ_DEPOSIT)
+        o.push()
+        o.deposit()
+        _compare(g, o, 1e-12)
+        assert np.array_equal(g.grid("rho"), o.Q)
+    m = g.moments()
+    assert np.array_equal(m["absorbed"], o.absorbed)
+    assert m["q_total"] == int(o.Q.sum())
+
+
+def test_rz_rotation_closed_form():
+    """Neutrals with an azimuthal velocity move on straight lines in 3D:
+    r_k = |(r0 + k v_r, k v_theta)| after k pushes (no field acts on them)."""
+    o = RZ(GEOM["nr"], GEOM["nz"], GEOM["h"], GEOM["tip_r"], GEOM["tip_h"], GEOM["apex_field"], GEOM["dt"],
+           GEOM["m_ion"])
+    rng = np.random.default_rng(3)
+    n = 500
+    r0 = rng.uniform(6, 20, n)
+    vr = rng.uniform(-0.4, 0.4, n)
+    vt = rng.uniform(-0.3, 0.3, n)
+    load = {2: {"r": r0, "z": np.full(n, 60.0), "vr": vr, "vt": vt, "vz": np.zeros(n)}}
+    g = rz.RZSimulation(**GEOM, load=load)
+    for k in range(1, 21):
+        g.step(1, rz.PIC_RZ_PUSH)
+        st = g.state()[2]
+        idx = st["id"].astype(np.int64)
+        want = np.hypot(r0[idx] + k * vr[idx], k * vt[idx])
+        np.testing.assert_allclose(st["r"], want, rtol=1e-12)
+        np.testing.assert_allclose(st["r"] * st["vt"], r0[idx] * vt[idx], rtol=1e-11)
+
+
+def test_rz_whole_steps():
+    """Ten steps of push, deposit and solve (to a relative residual of 1e-14,
+    the oracle solving directly): charge bit-exact, particles to 1e-9."""
+    g, o = _pair(seed=4, n=(20000, 2000, 0))
+    g.set_phi(o.phi)
+    g.step(1, rz.PIC_RZ_DEPOSIT | rz.PIC_RZ_SOLVE)
+    o.deposit()
+    o.solve()
+    for s in range(10):
+        g.step(1, rz.PIC_RZ_FULL)
+        o.step()
+        assert np.array_equal(g.grid("rho"), o.Q)
+        _compare(g, o, 1e-9)
+        phi = g.grid("phi")
+        assert np.abs(phi - o.phi).max() <= 1e-9 * np.abs(o.phi).max()
+    m = g.moments()
+    print("alive", m["n_alive"], "absorbed", m["absorbed"].sum(axis=1), "CG", m["last_cg_iters"], flush=True)
+    assert np.array_equal(m["absorbed"], o.absorbed)
