@@ -694,14 +694,22 @@ def batch_main(args, log):
         tuning = batch.autotune(items, log=log)
         batch.save_tuning(tuning, args.tuning)
     t0 = time.perf_counter()
-    b = batch.Batch(items, tuning=tuning)
+    b = batch.Batch(items, tuning=tuning, log=log)
     log(f"[bench] batch of {len(items)} instances ready ({time.perf_counter() - t0:.1f} s), "
         f"{sum(sum(c) for _, c in items)} particles")
     b.step(args.warmup)
     n0 = b.alive()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    b.step(args.steps)
+    # in chunks of 100 steps with a progress line after each
+    done = 0
+    while done < args.steps:
+        k = min(100, args.steps - done)
+        b.step(k)
+        done += k
+        if done < args.steps:
+            log(f"[bench] batch step {done} ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     n1 = b.alive()
     value = 0.5 * (n0 + n1) * args.steps / wall

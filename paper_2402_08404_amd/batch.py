@@ -66,7 +66,7 @@ class Batch:
     """Instances of a sweep, each a pic.Simulation on its own stream."""
 
     def __init__(self, items, kT_eV=(5.0, 1.0, 0.1), region="box", precision=pic.PIC_F32,
-                 solver=pic.PIC_SOLVER_MGCG, tuning: dict | None = None, step_rtol=1e-8, load_seed=7):
+                 solver=pic.PIC_SOLVER_MGCG, tuning: dict | None = None, step_rtol=1e-8, load_seed=7, log=None):
         self.sims = []
         self.items = items
         tuning = tuning or {}
@@ -82,6 +82,8 @@ class Batch:
             sim.step(1, pic.STEP_DEPOSIT)
             sim.solve(solver=solver, guess=pic.PIC_GUESS_PREVIOUS, rtol=step_rtol, maxit=100000)
             self.sims.append(sim)
+            if log:
+                log(f"[batch] instance {k} ready: {shape_key(cfg)}, {sum(counts)} particles")
         torch.cuda.synchronize()
         self._pool = ThreadPoolExecutor(max_workers=max(1, len(self.sims)))
 

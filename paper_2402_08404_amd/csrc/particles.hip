@@ -892,10 +892,7 @@ __global__ __launch_bounds__(64) void k_mcc_big(MccArgs<T> a) {
         uint32_t c = a.big[b];
         uint32_t o0 = a.off[c];
         int n = (int)(a.off[c + 1] - o0);
-        if (n > kBigCell) {
-            if (lane == 0) atomicCAS(&a.st->error, 0, PIC_E_CAPACITY);
-            continue;
-        }
+        if (n > kBigCell) continue;  // k_mcc_huge
         int P = 1;
         while (P < n) P <<= 1;
         for (int t = lane; t < P; t += 64) {
@@ -978,6 +975,115 @@ __global__ __launch_bounds__(64) void k_mcc_big(MccArgs<T> a) {
         }
         int tw = wave_sum(cnt[5 + k]);
         if (lane == 0 && tw) atomicAdd(&a.st->events_w[k], (unsigned long long)tw);
+    }
+}
+
+// Cells of more than kBigCell particles (a dense plasma near the tip): one
+// block of kHugeThreads per cell. The cell's bin entries are sorted by
+// (species, id) in place in global memory by a bitonic network whose
+// comparators all put the smaller key first (each merge starts with the
+// mirrored pairs), so the virtual +inf keys that pad the count to a power
+// of two never move and are never stored; the pair classes then run as in
+// k_mcc_big with the per-entry used flags in global memory (flags, indexed
+// by bin position).
+constexpr int kHugeThreads = 1024;
+
+__device__ inline uint64_t bin_key(uint2 e) { return ((uint64_t)(e.x >> 30) << 32) | e.y; }
+
+__device__ inline void huge_cmpx(uint2* e, int n, int i, int j) {
+    if (j >= n) return;  // e[j] is +inf
+    const uint2 x = e[i], y = e[j];
+    if (bin_key(x) > bin_key(y)) {
+        e[i] = y;
+        e[j] = x;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kHugeThreads) void k_mcc_huge(MccArgs<T> a, uint32_t* flags) {
+    __shared__ int sh[kHugeThreads / 64];
+    int cnt[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    const int tid = threadIdx.x;
+    const int64_t nbig = (int64_t)a.st->n_big;
+    for (int64_t b = blockIdx.x; b < nbig; b += gridDim.x) {
+        const uint32_t c = a.big[b];
+        const uint32_t o0 = a.off[c];
+        const int n = (int)(a.off[c + 1] - o0);
+        if (n <= kBigCell) continue;
+        uint2* e = a.bins + o0;
+        uint32_t* used = flags + o0;
+        int P = 1;
+        while (P < n) P <<= 1;
+        for (int k = 2; k <= P; k <<= 1) {
+            const int hk = k >> 1;
+            for (int t = tid; t < P / 2; t += kHugeThreads) {
+                const int base = (t / hk) * k, r = t % hk;
+                huge_cmpx(e, n, base + r, base + k - 1 - r);
+            }
+            __syncthreads();
+            for (int j = k >> 2; j > 0; j >>= 1) {
+                for (int t = tid; t < P / 2; t += kHugeThreads) {
+                    const int i = (t / j) * 2 * j + t % j;
+                    huge_cmpx(e, n, i, i + j);
+                }
+                __syncthreads();
+            }
+        }
+        int ne = 0, ni = 0;
+        for (int t = tid; t < n; t += kHugeThreads) {
+            const uint32_t sp = e[t].x >> 30;
+            ne += sp == 0;
+            ni += sp == 1;
+            used[t] = 0u;
+        }
+        ne = block_sum(ne, sh);
+        if (tid == 0) sh[0] = ne;
+        __syncthreads();
+        ne = sh[0];
+        __syncthreads();
+        ni = block_sum(ni, sh);
+        if (tid == 0) sh[0] = ni;
+        __syncthreads();
+        ni = sh[0];
+        __syncthreads();
+        const int nn = n - ne - ni;
+        for (int cls = 1; cls <= 2; ++cls) {
+            const int a0 = cls == 1 ? 0 : ne, na = cls == 1 ? ne : ni, b0 = ne + ni, nb = nn;
+            if (na > 0 && nb > 0) {
+                const bool a_proj = na <= nb;
+                const int P0 = a_proj ? a0 : b0, NP = a_proj ? na : nb;
+                const int T0 = a_proj ? b0 : a0, NT = a_proj ? nb : na;
+                const Draw2 dc = draw2(a.seed, linear_cell(a.g, c), a.step, cls == 1 ? kTagPair1 : kTagPair2, 0);
+                int shift = (int)floor(dc.a * (double)NT);
+                shift = shift > NT - 1 ? NT - 1 : shift;
+                const double pnull = pnull_of(a, cls, NT);
+                for (int i = tid; i < NP; i += kHugeThreads) {
+                    const int pi = P0 + i, ti = T0 + (shift + i) % NT;
+                    const int ai = a_proj ? pi : ti, bi = a_proj ? ti : pi;
+                    if (cls == 2 && used[bi]) continue;
+                    const uint32_t pid = e[pi].y;
+                    uint32_t nc = 0;
+                    const int kind =
+                        resolve_pair(a, cls, pid, e[ai].x & 0x3FFFFFFFu, e[bi].x & 0x3FFFFFFFu, NT, pnull, nc);
+                    if (kind) {
+                        used[bi] = 1u;
+                        a.nflag[e[bi].x & 0x3FFFFFFFu] = a.step + 1u;
+                        cnt[kind]++;
+                        cnt[5 + kind] += (int)nc;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int k = 1; k <= 3; ++k) {
+        const int t = block_sum(cnt[k], sh);
+        if (tid == 0 && t) {
+            atomicAdd(&a.st->events[k], (unsigned long long)t);
+            if (k == PIC_EV_IONIZE) atomicAdd(&a.st->n_prod_kind[0], (unsigned long long)t);
+        }
+        const int tw = block_sum(cnt[5 + k], sh);
+        if (tid == 0 && tw) atomicAdd(&a.st->events_w[k], (unsigned long long)tw);
     }
 }
 
@@ -1725,7 +1831,10 @@ __global__ __launch_bounds__(64) void k_pair_big(PairArgs<T> a) {
         const uint32_t c = a.big[b];
         const uint32_t o0 = a.off[c];
         const int n = (int)(a.off[c + 1] - o0);
-        if (n > kBigCell) continue;  // reported by the collision pass
+        if (n > kBigCell) {  // not supported by the pairing of this kernel
+            if (lane == 0) atomicCAS(&a.st->error, 0, PIC_E_CAPACITY);
+            continue;
+        }
         int P = 1;
         while (P < n) P <<= 1;
         for (int t = lane; t < P; t += 64) {
@@ -2016,6 +2125,7 @@ static hipError_t collide_t(pic_ctx* c, bool record) {
     hipLaunchKernelGGL(k_mcc_compact<T>, dim3(gm), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(k_mcc_cells<T>, dim3(side ? 256 : 2048), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(k_mcc_big<T>, dim3(1024), dim3(64), 0, c->stream, a);
+    hipLaunchKernelGGL(k_mcc_huge<T>, dim3(64), dim3(kHugeThreads), 0, c->stream, a, c->rank_flag);
     toc(c, tm);
     hipLaunchKernelGGL(k_fi_resolve<T>, dim3(grid_for(c->buf.cap[2])), dim3(kBlock), 0, c->stream, a, c->fi_list,
                        c->bitmap[1]);

@@ -252,6 +252,34 @@ def test_collide_big_cells():
     compare_states(cfg, g.state(), o.state(), 0.0, 1e-12)
 
 
+@pytest.mark.parametrize("precision", [F64, F32])
+def test_collide_huge_cells(precision):
+    """Cells of more than 4096 particles (the global-memory path that sorts
+    a cell's bin entries in place): two cells of about 6 000 electrons,
+    2 000 ions and 5 000 neutrals each, beside ordinary cells."""
+    cfg = W.tiny()
+    cfg.xs_el, cfg.xs_iz, cfg.xs_cx = W.constant_tables(2e-21, 1e-21, 3e-19)
+    load = dense_load(cfg, ncell=2, per=(6000, 2000, 5000), seed=17)
+    small = dense_load(cfg, ncell=300, per=(6, 2, 5), seed=18)
+    for k in load:
+        for q in load[k]:
+            load[k][q] = np.concatenate([load[k][q], small[k][q]])
+    g, o, load = _pair(cfg, load, precision)
+    phi = W.synthetic_potential(cfg, 100.0)
+    g.set_phi(phi)
+    o.set_phi(phi)
+    g.step(1, pic.STEP_DEPOSIT | pic.STEP_COLLIDE | pic.STEP_EVENTS)
+    o.collide()
+    ev_o = event_sets(o.last_events, o.last_fragile)
+    print("events", len(ev_o), flush=True)
+    assert len(ev_o) > 1000
+    assert event_sets(g.events(), o.last_fragile) == ev_o
+    assert g.moments()["error"] == 0
+    if not o.last_fragile:
+        tol = 1e-12 if precision == F64 else 2.0 ** -23
+        compare_states(cfg, g.state(), o.state(), 0.0, tol)
+
+
 @pytest.mark.parametrize("precision,az,field,steps", [(F64, 64, 13e9, 200), (F32, 64, 13e9, 200),
                                                        (F64, 512, 20e9, 60)])
 def test_emission_parity(precision, az, field, steps):
