@@ -1114,10 +1114,11 @@ int orc_collide(const orc_config* c, uint32_t step, int32_t flags, const double*
     if (flags & ORC_COLL_FI) {
         /* Field ionization (Sec. 2.3.4): a neutral ionizes in the step when
          * P dt > U, P from Eq. dfi at the local field. Readings: the field is
-         * taken at the post-push position; "reject all neutrals" above the
-         * barrier-suppression limit E > (3/2) xi^{3/2} means no field
-         * ionization is attempted for them; the products are placed as in
-         * impact ionization, the electron with the neutral's velocity. */
+         * taken at the post-push position; the paper leaves neutrals in
+         * fields above the barrier-suppression limit E > (3/2) xi^{3/2} out of
+         * the rate, read as: no field ionization is attempted for them; the
+         * products are placed as in impact ionization, the electron with the
+         * neutral's velocity. */
         orc_species* N = &sp[ORC_SP_NEU];
         double ebsi = 1.5 * pow(c->xi, 1.5);
         double dt_fs = c->dt * 1e15;
