@@ -3,8 +3,9 @@ particle-mesh step (Sec. 2.2: the axisymmetric vacuum mesh, the 2D3V method,
 particles rotated back into the r-z plane every step, reflection at the
 axis, removal at the cathode, the anode and the open side; leapfrog).
 
-TEST INFRASTRUCTURE ONLY: imported by tests/ only. Plain numpy and scipy;
-it shares no code with the GPU library.
+TEST INFRASTRUCTURE ONLY: imported by tests/ only. Plain numpy and scipy,
+with the 3D oracle's Philox draws and rate routines; it shares no code with
+the GPU library.
 
 Readings (the paper leaves the discretization to its references):
 - nodes at (r, z) = (i h, k h), i < nr, k < nz; the tip is the body of
@@ -27,12 +28,14 @@ Readings (the paper leaves the discretization to its references):
   reflection at the axis); removal: z <= 0 cathode, z >= nz - 1 anode,
   r >= nr - 1 side, inside the tip;
 - the deposit: bilinear weights in (r, z) quantized per axis to 2^-20, so a
-  particle deposits exactly 2^40 units of 2^-40 e onto its four nodes.
+  particle deposits exactly 2^40 units of 2^-40 e onto its four nodes;
+- collisions, field ionization and emission: see RZ.
 Positions are in grid units (r / h, z / h), velocities in grid units per
 step (v dt / h), with the azimuthal velocity v_theta as a third component.
 """
 from __future__ import annotations
 
+import ctypes as C
 import math
 
 import numpy as np
@@ -42,13 +45,38 @@ import scipy.sparse.linalg as spla
 
 FREE, DIR0, DIRV = 0, 1, 2
 ALIVE, CATHODE, ANODE, SIDE, TIP = 0, 1, 2, 3, 4
+TAG_MCC1, TAG_MCC2, TAG_PAIR1, TAG_PAIR2, TAG_FI, TAG_INJ = 1, 2, 3, 4, 5, 6
+XI_CU = 7.726380            # first ionization energy of Cu [eV]
 
 
 class RZ:
-    """The state of one axisymmetric instance: grid, potential, particles."""
+    """The state of one axisymmetric instance: grid, potential, particles.
 
-    def __init__(self, nr, nz, h, tip_r, tip_h, apex_field, dt, m_ion):
+    Collisions, field ionization and emission (collide, emit) follow the
+    readings of the 3D oracle (its Philox draws, cross-section tables, ADK
+    and Murphy-Good routines), with these for the axisymmetric mesh: the
+    particles of a cell (i, k) (between the nodes i, i + 1 and k, k + 1) are
+    paired as in a 3D cell, their (v_r, v_theta, v_z) taken as Cartesian
+    components (the azimuthal positions of a pair are not tracked, so the
+    local frames of the two are taken as one); the per-cell draw is keyed by
+    k (nr - 1) + i; the density is N_t over the annular cell volume
+    pi (2 i + 1) h^3; the emission patches are rings: fn_rings equal-area rings of the cap, then
+    rings one spacing high on the side, each with the Murphy-Good current at
+    phi(s + h n) / h and N = J A dt / e electrons, floor(N) plus one with
+    probability frac(N), placed uniformly on the ring 10^-3 spacings out
+    with zero velocity."""
+
+    def __init__(self, nr, nz, h, tip_r, tip_h, apex_field, dt, m_ion, seed=1, xs=None, xi=XI_CU,
+                 phi_w=4.5, fn_rings=16):
         self.nr, self.nz, self.h, self.dt, self.m_ion = nr, nz, h, dt, m_ion
+        self.seed, self.xi, self.phi_w, self.fn_rings = seed, xi, phi_w, fn_rings
+        # cross-section tables (emin, emax, el, iz, cx) on log-spaced energies
+        self.xs = xs
+        self.next_id = 0
+        self.step_no = 0
+        self.events = np.zeros(5, np.int64)
+        self.injected = 0
+        self.last_events = []
         self.R, self.H = tip_r / h, tip_h / h
         self.type = self.node_types()
         self.A = self.operator()
@@ -155,6 +183,239 @@ class RZ:
     def load(self, s, arrays, ids):
         self.sp[s] = {k: np.asarray(v, np.float64).copy() for k, v in arrays.items()}
         self.sp[s]["id"] = np.asarray(ids, np.uint32).copy()
+        if len(ids):
+            self.next_id = max(self.next_id, int(np.max(ids)) + 1)
+
+    # -- random numbers, rates (the 3D oracle's routines) ----------------------
+    def _c(self):
+        import oracle
+        if getattr(self, "_cfg", None) is None:
+            self._cfg = oracle._Config(phi_w=self.phi_w, xi=self.xi, h=self.h, dt=self.dt, seed=self.seed)
+            if self.xs is not None:
+                emin, emax = self.xs[0], self.xs[1]
+                self._tabs = [np.ascontiguousarray(t, np.float64) for t in self.xs[2:5]]
+                self._cfg.xs_n, self._cfg.xs_emin, self._cfg.xs_emax = len(self._tabs[0]), emin, emax
+            self._L = oracle.lib()
+        return self._L, self._cfg
+
+    def xs_at(self, k, E):
+        """Cross section k (0 elastic, 1 ionization, 2 charge exchange) at E
+        [eV]: the 3D oracle's table interpolation."""
+        L, c = self._c()
+        return L.orc_xs(C.byref(c), self._tabs[k], E)
+
+    def draw2(self, a, step, tag, sub):
+        import oracle
+        w = oracle.philox([a & 0xFFFFFFFF, step, tag, sub], [self.seed & 0xFFFFFFFF, self.seed >> 32])
+        return oracle.uniform(int(w[0]), int(w[1])), oracle.uniform(int(w[2]), int(w[3]))
+
+    def adk_rate(self, E_GVm):
+        """Eq. dfi: field-ionization rate per fs at E in GV/m."""
+        L, c = self._c()
+        return L.orc_adk_rate(C.byref(c), E_GVm)
+
+    def fn_current(self, F):
+        """Murphy-Good current density [A/m^2] at F [V/m] (f clamped at 1)."""
+        L, c = self._c()
+        cl = C.c_int(0)
+        return L.orc_fn_current(C.byref(c), F, C.byref(cl))
+
+    # -- emission ------------------------------------------------------------------
+    def patches(self):
+        zc = self.H - self.R
+        return self.fn_rings + max(int(math.ceil(zc)), 0)
+
+    def patch_point(self, p, ua):
+        """(r, z, n_r, n_z, area) of patch p at the uniform ua (grid units)."""
+        R, zc = self.R, self.H - self.R
+        if p < self.fn_rings:
+            ct = 1.0 - (p + ua) / self.fn_rings
+            st = math.sqrt(1.0 - ct * ct)
+            return R * st, zc + R * ct, st, ct, 2.0 * math.pi * R * R / self.fn_rings
+        q = p - self.fn_rings
+        zlo, zhi = float(q), min(q + 1.0, zc)
+        return R, zlo + ua * (zhi - zlo), 1.0, 0.0, 2.0 * math.pi * R * (zhi - zlo)
+
+    def emit(self):
+        """Fowler-Nordheim emission of one step; returns the number of
+        electrons added (ids in patch order)."""
+        new = {k: [] for k in ("r", "z", "vr", "vt", "vz", "id")}
+        for p in range(self.patches()):
+            r, z, nr_, nz_, area = self.patch_point(p, 0.5)
+            F = self.interp(self.phi, r + nr_, z + nz_) / self.h
+            N = self.fn_current(F) * area * self.h * self.h * self.dt / sc.e
+            u0, _ = self.draw2(p, self.step_no, TAG_INJ, 0)
+            k = int(math.floor(N)) + (1 if u0 < N - math.floor(N) else 0)
+            for j in range(k):
+                ua, _ = self.draw2(p, self.step_no, TAG_INJ, 1 + j)
+                r, z, nr_, nz_, _ = self.patch_point(p, ua)
+                new["r"].append(r + 1e-3 * nr_)
+                new["z"].append(z + 1e-3 * nz_)
+                for key in ("vr", "vt", "vz"):
+                    new[key].append(0.0)
+                new["id"].append(self.next_id)
+                self.next_id += 1
+        self._append(0, new)
+        self.injected += len(new["id"])
+        return len(new["id"])
+
+    def _append(self, s, new):
+        if self.sp[s] is None:
+            self.sp[s] = {k: np.zeros(0) for k in ("r", "z", "vr", "vt", "vz")}
+            self.sp[s]["id"] = np.zeros(0, np.uint32)
+        for k in ("r", "z", "vr", "vt", "vz"):
+            self.sp[s][k] = np.concatenate([self.sp[s][k], np.asarray(new[k], np.float64)])
+        self.sp[s]["id"] = np.concatenate([self.sp[s]["id"], np.asarray(new["id"], np.uint32)])
+
+    # -- collisions -------------------------------------------------------------------
+    @staticmethod
+    def _du(u, ct2, ph2):
+        """Eq. du: R^-1(theta, phi) [R^-1(theta', phi') - I] (0, 0, |u|)."""
+        um = math.sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2])
+        up = math.sqrt(u[0] * u[0] + u[1] * u[1])
+        ct, st = u[2] / um, up / um
+        cp, sp_ = (u[0] / up, u[1] / up) if up > 0.0 else (1.0, 0.0)
+        st2 = math.sqrt(1.0 - ct2 * ct2)
+        w0, w1, w2 = um * st2 * math.cos(ph2), um * st2 * math.sin(ph2), um * (ct2 - 1.0)
+        return (ct * cp * w0 - sp_ * w1 + st * cp * w2, ct * sp_ * w0 + cp * w1 + st * sp_ * w2, -st * w0 + ct * w2)
+
+    @staticmethod
+    def _iso(ct, ph):
+        st = math.sqrt(1.0 - ct * ct)
+        return st * math.cos(ph), st * math.sin(ph), ct
+
+    def cell_of(self, s):
+        d = self.sp[s]
+        i = np.clip(np.floor(d["r"]).astype(np.int64), 0, self.nr - 2)
+        k = np.clip(np.floor(d["z"]).astype(np.int64), 0, self.nz - 2)
+        return k * (self.nr - 1) + i
+
+    def collide(self):
+        """(e, Cu) pairs (elastic, impact ionization), then (Cu+, Cu) pairs
+        (charge exchange), field ionization of the neutrals without an
+        event, then the products (impact before field ionization, ascending
+        neutral id; ion id first, then the electron's). Returns the events
+        as (kind, id_a, id_b), kind 1 elastic, 2 ionization, 3 charge
+        exchange, 4 field ionization."""
+        h, dt = self.h, self.dt
+        V = ("vr", "vt", "vz")
+        for s in range(3):
+            if self.sp[s] is None:
+                self._append(s, {k: [] for k in ("r", "z", "vr", "vt", "vz", "id")})
+        cells = [self.cell_of(s) for s in range(3)]
+        used = [np.zeros(len(self.sp[s]["id"]), bool) for s in range(3)]
+        prods = []            # (kind, neutral id, neutral index, new electron velocity)
+        events = []
+        N = self.sp[2]
+        for cls in (1, 2):
+            sa = 0 if cls == 1 else 1
+            A = self.sp[sa]
+            ma, mb = (sc.m_e if cls == 1 else self.m_ion), self.m_ion
+            mu = ma * mb / (ma + mb)
+            for c in np.unique(cells[sa]):
+                ia = np.flatnonzero(cells[sa] == c)
+                ib = np.flatnonzero(cells[2] == c)
+                if len(ib) == 0:
+                    continue
+                ia = ia[np.argsort(A["id"][ia])]
+                ib = ib[np.argsort(N["id"][ib])]
+                a_proj = len(ia) <= len(ib)
+                P_, T_ = (ia, ib) if a_proj else (ib, ia)
+                NT = len(T_)
+                uc, _ = self.draw2(int(c), self.step_no, TAG_PAIR1 if cls == 1 else TAG_PAIR2, 0)
+                shift = min(int(math.floor(uc * NT)), NT - 1)
+                vol = math.pi * (2 * int(c % (self.nr - 1)) + 1) * h * h * h
+                n = NT / vol
+                for q, pp in enumerate(P_):
+                    tt = T_[(shift + q) % NT]
+                    xa, xb = (pp, tt) if a_proj else (tt, pp)
+                    if cls == 2 and used[2][xb]:
+                        continue
+                    pid = int((A if a_proj else N)["id"][pp])
+                    u = [(A[k][xa] - N[k][xb]) * h / dt for k in V]
+                    um = math.sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2])
+                    E = 0.5 * ma * um * um / sc.e
+                    if cls == 1:
+                        sig = [self.xs_at(0, E), self.xs_at(1, E) if E > self.xi else 0.0]
+                    else:
+                        sig = [self.xs_at(2, E)]
+                    stot = sum(sig)
+                    P = -math.expm1(-um * n * stot * dt)
+                    U1, U2 = self.draw2(pid, self.step_no, TAG_MCC1 if cls == 1 else TAG_MCC2, 0)
+                    if not U1 < P:
+                        continue
+                    proc, cum = len(sig) - 1, 0.0
+                    for kk, sg in enumerate(sig):
+                        cum += sg
+                        if U2 * stot < cum:
+                            proc = kk
+                            break
+                    used[sa][xa] = True
+                    used[2][xb] = True
+                    if cls == 2:
+                        for k in V:
+                            A[k][xa], N[k][xb] = N[k][xb], A[k][xa]
+                        events.append((3, int(A["id"][xa]), int(N["id"][xb])))
+                    elif proc == 0:
+                        u3, u4 = self.draw2(pid, self.step_no, TAG_MCC1, 1)
+                        du = self._du(u, 2.0 * u3 - 1.0, 2.0 * math.pi * u4)
+                        ka, kb = mu / ma * dt / h, mu / mb * dt / h
+                        for k, d in zip(V, du):
+                            A[k][xa] = A[k][xa] + ka * d
+                            N[k][xb] = N[k][xb] - kb * d
+                        events.append((1, int(A["id"][xa]), int(N["id"][xb])))
+                    else:
+                        c1, p1 = self.draw2(pid, self.step_no, TAG_MCC1, 1)
+                        c2, p2 = self.draw2(pid, self.step_no, TAG_MCC1, 2)
+                        u5, _ = self.draw2(pid, self.step_no, TAG_MCC1, 3)
+                        s1 = self._iso(2.0 * c1 - 1.0, 2.0 * math.pi * p1)
+                        s2 = self._iso(2.0 * c2 - 1.0, 2.0 * math.pi * p2)
+                        erem = E - self.xi
+                        e1 = u5 * erem
+                        e2 = erem - e1
+                        w1 = math.sqrt(2.0 * e1 * sc.e / sc.m_e)
+                        w2 = math.sqrt(2.0 * e2 * sc.e / sc.m_e)
+                        vn = [N[k][xb] * h / dt for k in V]
+                        for j, k in enumerate(V):
+                            A[k][xa] = (vn[j] + w1 * s1[j]) * dt / h
+                        prods.append((0, int(N["id"][xb]), xb, [(vn[j] + w2 * s2[j]) * dt / h for j in range(3)]))
+                        events.append((2, int(A["id"][xa]), int(N["id"][xb])))
+        # field ionization (Eq. dfi), none above the barrier-suppression field
+        ebsi = 1.5 * self.xi ** 1.5
+        for p in range(len(N["id"])):
+            if used[2][p]:
+                continue
+            er, ez = self.gather(N["r"][p], N["z"][p])
+            Eg = math.sqrt(er * er + ez * ez) * 1e-9
+            if Eg > ebsi:
+                continue
+            pdt = self.adk_rate(Eg) * (dt * 1e15)
+            U, _ = self.draw2(int(N["id"][p]), self.step_no, TAG_FI, 0)
+            if pdt > U:
+                used[2][p] = True
+                prods.append((1, int(N["id"][p]), p, [N[k][p] for k in V]))
+                events.append((4, 0xFFFFFFFF, int(N["id"][p])))
+        prods.sort(key=lambda t: (t[0], t[1]))
+        ions = {k: [] for k in ("r", "z", "vr", "vt", "vz", "id")}
+        els = {k: [] for k in ("r", "z", "vr", "vt", "vz", "id")}
+        gone = np.zeros(len(N["id"]), bool)
+        for kind, nid, xb, ve in prods:
+            for dst, v, idv in ((ions, [N[k][xb] for k in V], self.next_id), (els, ve, self.next_id + 1)):
+                dst["r"].append(N["r"][xb])
+                dst["z"].append(N["z"][xb])
+                for k, x in zip(V, v):
+                    dst[k].append(x)
+                dst["id"].append(idv)
+            self.next_id += 2
+            gone[xb] = True
+        self._append(1, ions)
+        self._append(0, els)
+        for k in N:
+            N[k] = N[k][~gone]
+        for kind, _, _ in events:
+            self.events[kind] += 1
+        self.last_events = events
+        return events
 
     def push(self):
         """One leapfrog step of every particle with rotation back into the r-z
@@ -222,7 +483,14 @@ class RZ:
         self.E = self.field(self.phi)
         return self.phi
 
-    def step(self):
+    def step(self, emit=False, collide=False):
+        """One step in the order of the 3D oracle: emission, push,
+        collisions and field ionization, deposit, solve."""
+        if emit:
+            self.emit()
         self.push()
+        if collide:
+            self.collide()
         self.deposit()
         self.solve()
+        self.step_no += 1

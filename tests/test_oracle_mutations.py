@@ -1,8 +1,9 @@
 """Each pin of the oracle tests must catch the plausible mistake it is there
 for. A copy of oracle.c with that one mistake planted is built on the CPU (or,
 for the merging of superparticles, written in Python, a copy of
-Oracle.merge), and the pin, run against the copy, must fail; the same pin
-passes on the real oracle in its own test module."""
+Oracle.merge, or of a method of the axisymmetric oracle), and the pin, run
+against the copy, must fail; the same pin passes on the real oracle in its
+own test module."""
 import inspect
 import os
 import textwrap
@@ -10,7 +11,9 @@ import textwrap
 import pytest
 
 import oracle
+import oracle.rz as orz
 import test_oracle_merging as M
+import test_oracle_rz_collide as RZC
 import test_oracle_pairing as PR
 import test_oracle_readings as R
 import test_oracle_surface as S
@@ -138,5 +141,47 @@ def test_merge_pin_catches_planted_mistake(monkeypatch, name, old, new, pin):
     ns = dict(vars(oracle))
     exec(src.replace(old, new), ns)
     monkeypatch.setattr(oracle.Oracle, "merge", ns["merge"])
+    with pytest.raises(AssertionError):
+        pin()
+
+
+# mistakes planted in the axisymmetric oracle: (name, method, text, planted
+# replacement, pin that must fail)
+RZ_MUTATIONS = [
+    ("cell volume without the ring factor", "collide",
+     "vol = math.pi * (2 * int(c % (self.nr - 1)) + 1) * h * h * h", "vol = math.pi * h * h * h",
+     RZC.pin_collision_rate),
+    ("elastic kick with the masses swapped", "collide",
+     "ka, kb = mu / ma * dt / h, mu / mb * dt / h", "ka, kb = mu / mb * dt / h, mu / ma * dt / h",
+     RZC.pin_elastic_conservation),
+    ("charge exchange copying one way", "collide",
+     "A[k][xa], N[k][xb] = N[k][xb], A[k][xa]", "A[k][xa] = N[k][xb]", RZC.pin_cx_swap),
+    ("ionization energy without the threshold", "collide", "erem = E - self.xi", "erem = E",
+     RZC.pin_ionization),
+    ("ion and electron ids swapped", "collide",
+     "(ions, [N[k][xb] for k in V], self.next_id), (els, ve, self.next_id + 1)",
+     "(ions, [N[k][xb] for k in V], self.next_id + 1), (els, ve, self.next_id)", RZC.pin_ionization),
+    ("field-ionization probability with dt in seconds", "collide",
+     "pdt = self.adk_rate(Eg) * (dt * 1e15)", "pdt = self.adk_rate(Eg) * dt", RZC.pin_field_ionization),
+    ("field ionization above the barrier-suppression field", "collide",
+     "if Eg > ebsi:\n            continue", "if False:\n            continue",
+     RZC.pin_field_ionization),
+    ("emission field taken on the surface", "emit",
+     "F = self.interp(self.phi, r + nr_, z + nz_) / self.h", "F = self.interp(self.phi, r, z) / self.h",
+     RZC.pin_emission_count),
+    ("no side rings", "patches", "return self.fn_rings + max(int(math.ceil(zc)), 0)", "return self.fn_rings",
+     RZC.pin_emission_geometry),
+    ("electrons started on the surface", "emit", "new[\"r\"].append(r + 1e-3 * nr_)", "new[\"r\"].append(r)",
+     RZC.pin_emission_geometry),
+]
+
+
+@pytest.mark.parametrize("name,method,old,new,pin", RZ_MUTATIONS, ids=[m[0] for m in RZ_MUTATIONS])
+def test_rz_pin_catches_planted_mistake(monkeypatch, name, method, old, new, pin):
+    src = textwrap.dedent(inspect.getsource(getattr(orz.RZ, method)))
+    assert src.count(old) == 1, f"mutation site not found: {name}"
+    ns = dict(vars(orz))
+    exec(src.replace(old, new), ns)
+    monkeypatch.setattr(orz.RZ, method, ns[method])
     with pytest.raises(AssertionError):
         pin()
