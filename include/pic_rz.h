@@ -7,8 +7,12 @@
  * Scope: the node grid with its tip, Poisson's equation in cylindrical
  * finite-volume form solved by FP64 conjugate gradients, the node field,
  * the gather, push, rotation and removal of electrons, Cu+ ions and Cu
- * neutrals, and the fixed-point charge deposit. The collision, emission and
- * surface stages of the 3D library are not part of this variant.
+ * neutrals, the fixed-point charge deposit, the pair collisions of Table
+ * colls (elastic e-Cu, impact ionization, charge exchange Cu+-Cu; Eqs. colp,
+ * du, newv), field ionization of Cu (Eq. dfi) and Fowler-Nordheim emission
+ * (Sec. 2.3.1). Superparticle weights, same-species and Coulomb collisions,
+ * recombination, evaporation and the circuit of the 3D library are not part
+ * of this variant.
  *
  * Discretization: nodes at (r, z) = (i h, k h), 0 <= i < nr, 0 <= k < nz,
  * node n = k * nr + i. Nodes of the plane k = 0 and inside the tip (a
@@ -31,6 +35,29 @@
  * angle atan2(y, x); removal (the slot's id set free) at z <= 0, z >=
  * nz - 1, r' >= nr - 1 or inside the tip. Deposit: bilinear weights per axis
  * quantized to 2^-20, every particle adds exactly 2^40 units of 2^-40 e.
+ *
+ * Collisions (PIC_RZ_COLLIDE), in the 3D library's pairing: the cell (i, k)
+ * lies between the nodes i, i + 1 and k, k + 1 (key k (nr - 1) + i, the
+ * per-cell draw's counter); the particles of a species in a cell, in
+ * ascending id order, pair with the other species' as in pic.h (the smaller
+ * count projects, targets shifted cyclically by floor(U_c N_t)); the density
+ * is N_t / (pi (2 i + 1) h^3), the annular cell volume; (v_r, v_theta, v_z)
+ * enter as Cartesian components. (e, Cu) first, then (Cu+, Cu) without the
+ * neutrals that had an event; then field ionization of the remaining
+ * neutrals below the barrier-suppression field 1.5 xi^1.5 GV/m; then the
+ * products, impact ionizations before field ionizations, each in ascending
+ * neutral id: the r-th product takes ion id next_id + 2 r and electron id
+ * next_id + 2 r + 1, appended at slot n[1] + r and n[0] + r; the ionized
+ * neutral's slot is freed. Emission (PIC_RZ_EMIT): fn_rings equal-area
+ * rings of the cap, then rings one spacing high on the cylinder, each with
+ * the Murphy-Good current J at the field phi(s + n) / h one spacing out
+ * along the normal from its mid point s; N = J A h^2 dt / e electrons, floor(N)
+ * plus one with probability frac(N) (draw (patch, step, 6, 0)); electron j
+ * at ring parameter U from draw (patch, step, 6, 1 + j), 10^-3 spacings out,
+ * at rest; ids continue from next_id in patch order. New particles are
+ * appended at the end of the species' slots, so within each species the
+ * slot order is the id order (which the pairing relies on): the initial ids
+ * of each species must increase strictly with the slot.
  */
 #ifndef PIC_RZ_H
 #define PIC_RZ_H
@@ -55,6 +82,13 @@ typedef struct pic_rz_config {
     int32_t maxit;         /* iteration limit of the solve inside pic_rz_step */
     int32_t reserved;
     double step_rtol;      /* tolerance of the solve inside pic_rz_step */
+    /* collisions, field ionization, emission */
+    uint64_t seed;         /* Philox key of every draw */
+    double xi;             /* ionization energy of Cu [eV] */
+    double phi_w;          /* work function [eV] */
+    double xs_emin, xs_emax; /* energy range of the cross-section tables [eV], log-spaced */
+    int32_t xs_n;          /* table length, >= 2 (0: no tables; PIC_RZ_COLLIDE then fails) */
+    int32_t fn_rings;      /* rings on the cap (0: no emission; PIC_RZ_EMIT then fails) */
 } pic_rz_config;
 
 typedef struct pic_rz_buffers {
@@ -75,6 +109,8 @@ typedef struct pic_rz_buffers {
     uint8_t* node_type;    /* nr*nz: 0 free, 1 held at 0 V, 2 held at V0 */
     void* scratch;         /* pic_rz_scratch_size bytes, 256-byte aligned */
     size_t scratch_bytes;
+    const double* xs;      /* 3 * xs_n cross sections [m^2]: elastic, ionization,
+                              charge exchange at xs_emin (xs_emax / xs_emin)^(k / (xs_n - 1)) */
 } pic_rz_buffers;
 
 typedef struct pic_rz_moments_t {
@@ -86,6 +122,10 @@ typedef struct pic_rz_moments_t {
     double apex_field1;      /* F1, apex field per volt of anode potential [1/m] */
     int32_t last_cg_iters;   /* iterations of the last solve */
     int32_t error;           /* sticky error code */
+    int64_t n_slots[3];      /* slots in use per species (alive and freed) */
+    int64_t events[5];       /* cumulative: 1 elastic, 2 impact ionization, 3 charge exchange, 4 field ionization */
+    int64_t injected;        /* cumulative emitted electrons */
+    int64_t next_id;         /* id of the next new particle */
 } pic_rz_moments_t;
 
 typedef struct pic_rz_ctx pic_rz_ctx;
@@ -96,19 +136,30 @@ typedef struct pic_rz_ctx pic_rz_ctx;
 #define PIC_RZ_SOLVE 4u    /* Poisson solve to step_rtol from the previous potential, then the node field */
 #define PIC_RZ_ADVANCE 8u  /* count the step */
 #define PIC_RZ_FIELD 16u   /* without PIC_RZ_SOLVE: the node field of the current phi */
+#define PIC_RZ_EMIT 32u    /* field emission (before the push) */
+#define PIC_RZ_COLLIDE 64u /* collisions, field ionization, products (after the push) */
 #define PIC_RZ_FULL 15u
+#define PIC_RZ_ALL 111u    /* PIC_RZ_FULL with emission and collisions */
 
 /* Bytes of work memory for cfg and cap. Invalid config: PIC_E_INVALID_ARG. */
 pic_status pic_rz_scratch_size(const pic_rz_config* cfg, const int64_t cap[3], size_t* bytes);
 
 /* Create a context on hip_stream (NULL: the default stream): node types, the
  * unit-anode solve (to laplace_rtol) into phi1, V0, phi = V0 phi1 and its
- * field. Buffers are caller-owned; the context keeps their pointers.
- * Errors: PIC_E_INVALID_ARG (config, buffers, n > cap), PIC_E_NOT_CONVERGED,
+ * field; next_id = one above the largest initial id (0 without particles).
+ * Buffers are caller-owned; the context keeps their pointers.
+ * Errors: PIC_E_INVALID_ARG (config, buffers, n > cap, initial ids of a
+ * species not strictly increasing with the slot or free), PIC_E_NOT_CONVERGED,
  * PIC_E_HIP. */
 pic_status pic_rz_init(const pic_rz_config* cfg, const pic_rz_buffers* bufs, void* hip_stream, pic_rz_ctx** out);
 
-/* nsteps steps of the stages in flags, in the order push, deposit, solve. */
+/* nsteps steps of the stages in flags, in the order emission, push,
+ * collisions, deposit, solve. Draws are keyed by the step counter, which
+ * PIC_RZ_ADVANCE counts. New particles that would overflow a species'
+ * capacity, or ids that would reach 0xFFFFFFFF, are not made: the stage
+ * sets the sticky error and the call returns PIC_E_CAPACITY (or
+ * PIC_E_OVERFLOW for ids) after its steps. PIC_E_INVALID_ARG for
+ * PIC_RZ_COLLIDE without tables or PIC_RZ_EMIT without rings. */
 pic_status pic_rz_step(pic_rz_ctx* ctx, int32_t nsteps, uint32_t flags);
 
 /* Solve for the charge in rho from the current phi until ||b - A phi|| <=

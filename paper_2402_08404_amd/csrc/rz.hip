@@ -2,8 +2,10 @@
 // step (Sec. 2.2): node types of the axisymmetric tip, Poisson's equation in
 // cylindrical finite-volume form by FP64 conjugate gradients, the node
 // field, gather + leapfrog push with the rotation back into the r-z plane,
-// removal, and the fixed-point deposit. The discretization is stated in
-// pic_rz.h.
+// removal, the fixed-point deposit, pair collisions over the annular cells
+// (Table colls, Eqs. colp, du, newv), field ionization (Eq. dfi) and
+// Fowler-Nordheim emission from rings of the tip (Sec. 2.3.1). The
+// discretization and the pairing are stated in pic_rz.h.
 #include <algorithm>
 #include <cmath>
 #include <string>
@@ -14,6 +16,8 @@
 namespace pic_rz {
 
 using pic::clampi;
+using pic::Draw2;
+using pic::draw2;
 using pic::kBlock;
 using pic::kDead;
 using pic::kEps0;
@@ -24,10 +28,20 @@ using pic::kQe;
 constexpr int kCgBlocks = 256;  // blocks of the CG kernels (one partial each, summed in block order)
 constexpr uint8_t kFree = 0, kHeld0 = 1, kHeldV = 2;  // node types
 
+constexpr int kScanBlock = 1024;  // threads of the single-block scans
+
 struct State {
     unsigned long long absorbed[3][5];
     double rr, bb, pq, alpha, beta, rtol;
     int it, maxit, done, error;
+    unsigned long long n[3];       // slots in use per species
+    unsigned long long next_id;    // id of the next new particle
+    unsigned long long events[5];  // 1 elastic, 2 impact ionization, 3 charge exchange, 4 field ionization
+    unsigned long long injected;
+    unsigned long long base_n[2], base_id;  // first electron / ion slot and first id of the stage's new particles
+    unsigned long long total;      // total of the last scan
+    int skip;                      // the stage's new particles did not fit
+    int pad;
 };
 
 struct Geo {
@@ -245,7 +259,6 @@ struct PushArgs {
     Geo g;
     double *r, *z, *vr, *vt, *vz;
     uint32_t* id;
-    int64_t n;
     const double* E;
     double kq;  // (q / m) dt^2 / h
     int sp;
@@ -254,7 +267,7 @@ struct PushArgs {
 
 __global__ __launch_bounds__(kBlock) void k_push(PushArgs a) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= a.n || a.id[p] == kDead) return;
+    if (p >= (int64_t)a.st->n[a.sp] || a.id[p] == kDead) return;
     const Geo& g = a.g;
     double r = a.r[p], z = a.z[p], vr = a.vr[p], vt = a.vt[p], vz = a.vz[p];
     if (a.kq != 0.0) {
@@ -305,9 +318,9 @@ __global__ void k_zero_rho(int64_t* rho, int64_t nn) {
 }
 
 __global__ __launch_bounds__(kBlock) void k_deposit(Geo g, const double* r, const double* z, const uint32_t* id,
-                                                     int64_t n, int64_t sign, int64_t* rho) {
+                                                     const State* st, int sp, int64_t sign, int64_t* rho) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n || id[p] == kDead) return;
+    if (p >= (int64_t)st->n[sp] || id[p] == kDead) return;
     const double R = r[p], Z = z[p];
     const int i = clampi((int)floor(R), 0, g.nr - 2), k = clampi((int)floor(Z), 0, g.nz - 2);
     const int64_t qr = pic::quantize(R - i, 20), qz = pic::quantize(Z - k, 20);
@@ -320,9 +333,9 @@ __global__ __launch_bounds__(kBlock) void k_deposit(Geo g, const double* r, cons
     atomicAdd(q + n0 + g.nr + 1, (unsigned long long)(sign * qr * qz));
 }
 
-__global__ void k_counts(const uint32_t* id, int64_t n, unsigned long long* out) {
+__global__ void k_counts(const uint32_t* id, const State* st, int sp, unsigned long long* out) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool alive = p < n && id[p] != kDead;
+    const bool alive = p < (int64_t)st->n[sp] && id[p] != kDead;
     const unsigned long long m = __ballot(alive);
     if ((threadIdx.x & 63) == 0 && m) atomicAdd(out, (unsigned long long)__popcll(m));
 }
@@ -335,30 +348,525 @@ __global__ void k_qsum(const int64_t* rho, int64_t nn, unsigned long long* out) 
     if ((threadIdx.x & 63) == 0 && s) atomicAdd(out, (unsigned long long)s);
 }
 
+// ---------------------------------------------------------------------------
+// Initial ids: strictly increasing with the slot within a species (and none
+// free); next_id one above the largest.
+__global__ void k_check_ids(const uint32_t* id, int64_t n, State* st) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const uint32_t v = id[p];
+    if (v == kDead || (p + 1 < n && v >= id[p + 1])) atomicOr(&st->skip, 1);
+    if (p + 1 == n) atomicMax(&st->next_id, (unsigned long long)v + 1ull);
+}
+
+// Exclusive prefix sums of m counts in one block of kScanBlock threads, in
+// chunks of 4 kScanBlock (each thread a run of four, wavefront shuffles, the
+// wavefront totals in shared memory); the grand total goes to st->total.
+template <typename TO>
+__global__ __launch_bounds__(kScanBlock) void k_scan(const uint32_t* in, TO* out, int64_t m, State* st) {
+    __shared__ unsigned long long wsum[kScanBlock / 64];
+    __shared__ unsigned long long carry_s;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int64_t base = 0; base < m; base += 4 * kScanBlock) {
+        const int64_t i0 = base + 4 * (int64_t)threadIdx.x;
+        unsigned long long v[4], run = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = i0 + k < m ? (unsigned long long)in[i0 + k] : 0ull;
+            run += v[k];
+        }
+        unsigned long long x = run;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
+        __syncthreads();
+        unsigned long long pre = carry_s, tot = 0;
+        for (int q = 0; q < kScanBlock / 64; ++q) {
+            pre += q < w ? wsum[q] : 0ull;
+            tot += wsum[q];
+        }
+        pre += x - run;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (i0 + k < m) out[i0 + k] = (TO)pre;
+            pre += v[k];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) st->total = carry_s;
+}
+
+__global__ void k_zero_u32(uint32_t* x, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0u;
+}
+
+struct CollArgs {
+    Geo g;
+    int64_t nc;        // cells (nr - 1) (nz - 1)
+    double *r[3], *z[3], *vr[3], *vt[3], *vz[3];
+    uint32_t* id[3];
+    int64_t off[3];    // offset of each species in the per-slot work arrays
+    int64_t cap[3];
+    State* st;
+    uint32_t* cnt;     // 3 nc particles per (species, cell)
+    uint32_t* fill;    // 3 nc placement counters
+    uint32_t* start;   // 3 nc exclusive prefix of cnt
+    uint32_t* seg;     // slots grouped by (species, cell), unordered within a cell
+    uint32_t* sorted;  // the same, ascending slot (= id) order within a cell
+    int32_t* cellof;   // cell of every slot (-1 free)
+    uint8_t* used;     // the slot's particle had an event this step
+    uint8_t* pflag;    // neutral slot: 1 impact ionization, 2 field ionization
+    double* ve;        // neutral slot: new electron's velocity of an impact ionization
+    uint32_t* bcnt;    // per block of neutral slots: impact, then field-ionization counts
+    uint32_t* bpre;    // their exclusive prefix
+    int64_t nblk;      // blocks of neutral slots
+    const double* E;
+    const double* xs;
+    int xs_n;
+    double xs_emin, xs_lnr;
+    double h, dt, m_ion, xi;
+    uint64_t seed;
+    uint32_t step;
+    double adk_c, adk_e, x32, dt_fs, ebsi;
+};
+
+__device__ inline int cell_index(const Geo& g, double r, double z) {
+    const int i = clampi((int)floor(r), 0, g.nr - 2), k = clampi((int)floor(z), 0, g.nz - 2);
+    return k * (g.nr - 1) + i;
+}
+
+// cell of every slot in use, counts per (species, cell); clears the flags
+__global__ __launch_bounds__(kBlock) void k_cells(CollArgs a, int s) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (int64_t)a.st->n[s]) return;
+    int32_t c = -1;
+    if (a.id[s][p] != kDead) {
+        c = cell_index(a.g, a.r[s][p], a.z[s][p]);
+        atomicAdd(&a.cnt[s * a.nc + c], 1u);
+    }
+    a.cellof[a.off[s] + p] = c;
+    a.used[a.off[s] + p] = 0;
+    if (s == 2) a.pflag[p] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_place(CollArgs a, int s) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (int64_t)a.st->n[s]) return;
+    const int32_t c = a.cellof[a.off[s] + p];
+    if (c < 0) return;
+    const int64_t key = s * a.nc + c;
+    a.seg[a.start[key] + atomicAdd(&a.fill[key], 1u)] = (uint32_t)p;
+}
+
+// Each grouped slot's rank among its cell's slots (the number of smaller
+// ones) gives its place in ascending order. The work is quadratic in the
+// particles of a cell; the lanes of a wavefront that share a cell read the
+// same addresses together.
+__global__ __launch_bounds__(kBlock) void k_rank(CollArgs a) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= (int64_t)a.st->total) return;  // the particles grouped, from the scan of the counts
+    const int s = j < (int64_t)a.start[a.nc] ? 0 : (j < (int64_t)a.start[2 * a.nc] ? 1 : 2);
+    const uint32_t p = a.seg[j];
+    const int64_t key = s * a.nc + a.cellof[a.off[s] + p];
+    const int64_t b = a.start[key], m = a.cnt[key];
+    int64_t rank = 0;
+    for (int64_t k = 0; k < m; ++k) rank += a.seg[b + k] < p ? 1 : 0;
+    a.sorted[b + rank] = p;
+}
+
+__device__ inline double xs_at(const CollArgs& a, int k, double E) {
+    const double* tab = a.xs + (int64_t)k * a.xs_n;
+    const int n = a.xs_n;
+    if (E <= a.xs_emin) return tab[0];
+    if (E >= a.xs_emin * exp(a.xs_lnr)) return tab[n - 1];
+    const double t = log(E / a.xs_emin) / a.xs_lnr * (double)(n - 1);
+    int q = (int)floor(t);
+    q = q > n - 2 ? n - 2 : (q < 0 ? 0 : q);
+    const double f = t - q;
+    return tab[q] + f * (tab[q + 1] - tab[q]);
+}
+
+__device__ inline void iso(double ct, double ph, double out[3]) {
+    const double st = sqrt(1.0 - ct * ct);
+    out[0] = st * cos(ph);
+    out[1] = st * sin(ph);
+    out[2] = ct;
+}
+
+// Pairs of class cls (1: e-Cu, 2: Cu+-Cu), one thread per particle of the
+// charged species; each pair has one thread, so every particle is written by
+// at most one thread of the class.
+__global__ __launch_bounds__(kBlock) void k_pair(CollArgs a, int cls) {
+    const int sa = cls == 1 ? 0 : 1;
+    const int64_t j = (int64_t)a.start[sa * a.nc] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= (int64_t)a.start[(sa + 1) * a.nc]) return;
+    const uint32_t pa0 = a.sorted[j];
+    const int32_t c = a.cellof[a.off[sa] + pa0];
+    const int64_t NA = a.cnt[sa * a.nc + c], NB = a.cnt[2 * a.nc + c];
+    if (NB == 0) return;
+    const int64_t qa = j - (int64_t)a.start[sa * a.nc + c];
+    const int64_t bB = a.start[2 * a.nc + c];
+    const bool a_proj = NA <= NB;
+    const int64_t NT = a_proj ? NB : NA;
+    const double uc = draw2(a.seed, (uint32_t)c, a.step, cls == 1 ? pic::kTagPair1 : pic::kTagPair2, 0).a;
+    int64_t shift = (int64_t)floor(uc * (double)NT);
+    if (shift > NT - 1) shift = NT - 1;
+    uint32_t pb;
+    if (a_proj) {
+        pb = a.sorted[bB + (shift + qa) % NT];
+    } else {
+        const int64_t q = (qa - shift + NA) % NA;
+        if (q >= NB) return;
+        pb = a.sorted[bB + q];
+    }
+    const uint32_t pa = pa0;
+    if (cls == 2 && a.used[a.off[2] + pb]) return;
+    const uint32_t pid = a_proj ? a.id[sa][pa] : a.id[2][pb];
+    const double h = a.h, dt = a.dt;
+    double* AV[3] = {a.vr[sa], a.vt[sa], a.vz[sa]};
+    double* BV[3] = {a.vr[2], a.vt[2], a.vz[2]};
+    const double vA[3] = {AV[0][pa], AV[1][pa], AV[2][pa]};
+    const double vB[3] = {BV[0][pb], BV[1][pb], BV[2][pb]};
+    const double u[3] = {(vA[0] - vB[0]) * h / dt, (vA[1] - vB[1]) * h / dt, (vA[2] - vB[2]) * h / dt};
+    const double um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    const double ma = cls == 1 ? kMe : a.m_ion, mb = a.m_ion;
+    const double E = 0.5 * ma * um * um / kQe;
+    double sig0, sig1 = 0.0;
+    if (cls == 1) {
+        sig0 = xs_at(a, 0, E);
+        sig1 = E > a.xi ? xs_at(a, 1, E) : 0.0;
+    } else {
+        sig0 = xs_at(a, 2, E);
+    }
+    const double stot = sig0 + sig1;
+    const int i = c % (a.g.nr - 1);
+    const double vol = kPi * (double)(2 * i + 1) * h * h * h;
+    const double n = (double)NT / vol;
+    const double P = -expm1(-um * n * stot * dt);
+    const Draw2 d = draw2(a.seed, pid, a.step, cls == 1 ? pic::kTagMcc1 : pic::kTagMcc2, 0);
+    if (!(d.a < P)) return;
+    int proc = cls == 1 ? 1 : 0;
+    if (cls == 1 && d.b * stot < sig0) proc = 0;
+    a.used[a.off[sa] + pa] = 1;
+    a.used[a.off[2] + pb] = 1;
+    if (cls == 2) {
+        for (int k = 0; k < 3; ++k) {
+            AV[k][pa] = vB[k];
+            BV[k][pb] = vA[k];
+        }
+        atomicAdd(&a.st->events[3], 1ull);
+        return;
+    }
+    if (proc == 0) {
+        // Eq. du: R^-1(theta, phi) [R^-1(theta', phi') - I] (0, 0, |u|)
+        const Draw2 r = draw2(a.seed, pid, a.step, pic::kTagMcc1, 1);
+        const double ct2 = 2.0 * r.a - 1.0, ph2 = 2.0 * kPi * r.b;
+        const double up = sqrt(u[0] * u[0] + u[1] * u[1]);
+        const double ct = u[2] / um, st = up / um;
+        double cp = 1.0, sp = 0.0;
+        if (up > 0.0) {
+            cp = u[0] / up;
+            sp = u[1] / up;
+        }
+        const double st2 = sqrt(1.0 - ct2 * ct2);
+        const double w0 = um * st2 * cos(ph2), w1 = um * st2 * sin(ph2), w2 = um * (ct2 - 1.0);
+        const double du[3] = {ct * cp * w0 - sp * w1 + st * cp * w2, ct * sp * w0 + cp * w1 + st * sp * w2,
+                              -st * w0 + ct * w2};
+        const double mu = ma * mb / (ma + mb);
+        const double ka = mu / ma * dt / h, kb = mu / mb * dt / h;
+        for (int k = 0; k < 3; ++k) {
+            AV[k][pa] = vA[k] + ka * du[k];
+            BV[k][pb] = vB[k] - kb * du[k];
+        }
+        atomicAdd(&a.st->events[1], 1ull);
+        return;
+    }
+    // impact ionization: in the neutral's frame the energy above xi is
+    // shared as U5 : 1 - U5, both electrons leave isotropically
+    const Draw2 r1 = draw2(a.seed, pid, a.step, pic::kTagMcc1, 1);
+    const Draw2 r2 = draw2(a.seed, pid, a.step, pic::kTagMcc1, 2);
+    const Draw2 r3 = draw2(a.seed, pid, a.step, pic::kTagMcc1, 3);
+    double s1[3], s2[3];
+    iso(2.0 * r1.a - 1.0, 2.0 * kPi * r1.b, s1);
+    iso(2.0 * r2.a - 1.0, 2.0 * kPi * r2.b, s2);
+    const double erem = E - a.xi;
+    const double e1 = r3.a * erem, e2 = erem - e1;
+    const double w1 = sqrt(2.0 * e1 * kQe / kMe), w2 = sqrt(2.0 * e2 * kQe / kMe);
+    const double vn[3] = {vB[0] * h / dt, vB[1] * h / dt, vB[2] * h / dt};
+    for (int k = 0; k < 3; ++k) {
+        AV[k][pa] = (vn[k] + w1 * s1[k]) * dt / h;
+        a.ve[3 * (int64_t)pb + k] = (vn[k] + w2 * s2[k]) * dt / h;
+    }
+    a.pflag[pb] = 1;
+    atomicAdd(&a.st->events[2], 1ull);
+}
+
+__device__ inline double bilinear(const Geo& g, const double* f, int stride, int comp, double r, double z) {
+    const int i = clampi((int)floor(r), 0, g.nr - 2), k = clampi((int)floor(z), 0, g.nz - 2);
+    const double fr = r - i, fz = z - k;
+    const int64_t n = (int64_t)k * g.nr + i;
+    return (1 - fr) * (1 - fz) * f[stride * n + comp] + fr * (1 - fz) * f[stride * (n + 1) + comp] +
+           (1 - fr) * fz * f[stride * (n + g.nr) + comp] + fr * fz * f[stride * (n + g.nr + 1) + comp];
+}
+
+// Field ionization (Eq. dfi) of the neutrals without an event: rate per fs
+// at the local field in GV/m, none above the barrier-suppression field.
+__global__ __launch_bounds__(kBlock) void k_fi(CollArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (int64_t)a.st->n[2] || a.id[2][p] == kDead || a.used[a.off[2] + p]) return;
+    const double er = bilinear(a.g, a.E, 2, 0, a.r[2][p], a.z[2][p]);
+    const double ez = bilinear(a.g, a.E, 2, 1, a.r[2][p], a.z[2][p]);
+    const double Eg = sqrt(er * er + ez * ez) * 1e-9;
+    if (Eg > a.ebsi || !(Eg > 0.0)) return;
+    const double pdt = a.adk_c * pow(20.5 * a.x32 / Eg, a.adk_e) * exp(-6.83 * a.x32 / Eg) * a.dt_fs;
+    if (pdt > draw2(a.seed, a.id[2][p], a.step, pic::kTagFi, 0).a) {
+        a.pflag[p] = 2;
+        a.used[a.off[2] + p] = 1;
+        atomicAdd(&a.st->events[4], 1ull);
+    }
+}
+
+// Per block of neutral slots: the impact (bcnt[b]) and field-ionization
+// (bcnt[nblk + b]) products; with the exclusive prefix of the concatenation
+// the r-th product of either kind follows in the required order.
+__device__ inline void block_flag_ranks(uint8_t f, uint32_t& rank, uint32_t tot[2]) {
+    __shared__ uint32_t wc[2][kBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t m1 = __ballot(f == 1), m2 = __ballot(f == 2);
+    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    if (lane == 0) {
+        wc[0][w] = (uint32_t)__popcll(m1);
+        wc[1][w] = (uint32_t)__popcll(m2);
+    }
+    __syncthreads();
+    uint32_t pre[2] = {0, 0};
+    tot[0] = tot[1] = 0;
+    for (int q = 0; q < kBlock / 64; ++q) {
+        pre[0] += q < w ? wc[0][q] : 0u;
+        pre[1] += q < w ? wc[1][q] : 0u;
+        tot[0] += wc[0][q];
+        tot[1] += wc[1][q];
+    }
+    rank = f == 1 ? pre[0] + (uint32_t)__popcll(m1 & lt) : pre[1] + (uint32_t)__popcll(m2 & lt);
+}
+
+__global__ __launch_bounds__(kBlock) void k_prod_count(CollArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint8_t f = p < (int64_t)a.st->n[2] ? a.pflag[p] : 0;
+    uint32_t rank, tot[2];
+    block_flag_ranks(f, rank, tot);
+    if (threadIdx.x == 0) {
+        a.bcnt[blockIdx.x] = tot[0];
+        a.bcnt[a.nblk + blockIdx.x] = tot[1];
+    }
+}
+
+// room for T new electrons and ions with 2 T ids (kind 0), or T electrons
+// with T ids (kind 1: emission)
+__global__ void k_commit(State* st, int kind, int64_t cap0, int64_t cap1) {
+    if (threadIdx.x != 0) return;
+    const unsigned long long T = st->total;
+    st->skip = 0;
+    if (T == 0) return;
+    const unsigned long long ids = kind == 0 ? 2 * T : T;
+    if (st->n[0] + T > (unsigned long long)cap0 || (kind == 0 && st->n[1] + T > (unsigned long long)cap1)) {
+        st->skip = 1;
+        if (st->error == 0) st->error = PIC_E_CAPACITY;
+        return;
+    }
+    if (st->next_id + ids > (unsigned long long)kDead) {
+        st->skip = 1;
+        if (st->error == 0) st->error = PIC_E_OVERFLOW;
+        return;
+    }
+    st->base_n[0] = st->n[0];
+    st->base_n[1] = st->n[1];
+    st->base_id = st->next_id;
+    st->n[0] += T;
+    if (kind == 0) st->n[1] += T;
+    st->next_id += ids;
+    if (kind == 1) st->injected += T;
+}
+
+__global__ __launch_bounds__(kBlock) void k_prod_place(CollArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint8_t f = p < (int64_t)a.st->n[2] ? a.pflag[p] : 0;
+    uint32_t rank, tot[2];
+    block_flag_ranks(f, rank, tot);
+    if (f == 0 || a.st->skip) return;
+    const uint64_t r = (uint64_t)a.bpre[(f == 1 ? 0 : a.nblk) + blockIdx.x] + rank;
+    const uint64_t si = a.st->base_n[1] + r, se = a.st->base_n[0] + r;
+    const uint32_t idi = (uint32_t)(a.st->base_id + 2 * r);
+    a.r[1][si] = a.r[2][p];
+    a.z[1][si] = a.z[2][p];
+    a.vr[1][si] = a.vr[2][p];
+    a.vt[1][si] = a.vt[2][p];
+    a.vz[1][si] = a.vz[2][p];
+    a.id[1][si] = idi;
+    a.r[0][se] = a.r[2][p];
+    a.z[0][se] = a.z[2][p];
+    if (f == 1) {
+        a.vr[0][se] = a.ve[3 * p];
+        a.vt[0][se] = a.ve[3 * p + 1];
+        a.vz[0][se] = a.ve[3 * p + 2];
+    } else {
+        a.vr[0][se] = a.vr[2][p];
+        a.vt[0][se] = a.vt[2][p];
+        a.vz[0][se] = a.vz[2][p];
+    }
+    a.id[0][se] = idi + 1u;
+    a.id[2][p] = kDead;
+}
+
+// ---------------------------------------------------------------------------
+// Field emission from rings of the tip surface
+struct EmitArgs {
+    Geo g;
+    const double* phi;
+    int rings;
+    int64_t npatch;
+    double h, dt, phi_w, phi_w15, fn_a, fn_b, fn_cs2;
+    uint64_t seed;
+    uint32_t step;
+    int64_t cap0;
+    uint32_t* cnt;    // electrons of each patch
+    uint64_t* offs;   // their exclusive prefix
+    double *r, *z, *vr, *vt, *vz;
+    uint32_t* id;
+    State* st;
+};
+
+// point of patch p at the ring parameter ua: {r, z, n_r, n_z, area}
+__device__ inline void ring_point(const EmitArgs& a, int64_t p, double ua, double out[5]) {
+    const double R = a.g.R, zc = a.g.H - a.g.R;
+    if (p < a.rings) {
+        const double ct = 1.0 - ((double)p + ua) / (double)a.rings;
+        const double st = sqrt(1.0 - ct * ct);
+        out[0] = R * st;
+        out[1] = zc + R * ct;
+        out[2] = st;
+        out[3] = ct;
+        out[4] = 2.0 * kPi * R * R / (double)a.rings;
+    } else {
+        const int64_t q = p - a.rings;
+        const double zlo = (double)q, zhi = fmin((double)(q + 1), zc);
+        out[0] = R;
+        out[1] = zlo + ua * (zhi - zlo);
+        out[2] = 1.0;
+        out[3] = 0.0;
+        out[4] = 2.0 * kPi * R * (zhi - zlo);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_emit_count(EmitArgs a) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.npatch) return;
+    double q[5];
+    ring_point(a, p, 0.5, q);
+    const double F = bilinear(a.g, a.phi, 1, 0, q[0] + q[2], q[1] + q[3]) / a.h;
+    double J = 0.0;
+    if (F > 0.0) {
+        double f = a.fn_cs2 * F / (a.phi_w * a.phi_w);
+        if (f > 1.0) f = 1.0;
+        const double lf = log(f);
+        const double v = 1.0 - f + (f / 6.0) * lf;
+        const double t = 1.0 + f / 9.0 - (f / 18.0) * lf;
+        J = a.fn_a * F * F / (a.phi_w * t * t) * exp(-v * a.fn_b * a.phi_w15 / F);
+    }
+    const double N = J * q[4] * a.h * a.h * a.dt / kQe;
+    const double fl = floor(N);
+    // beyond the capacity the count only has to overflow it
+    const double lim = (double)a.cap0 + 1.0;
+    int64_t k = fl < lim ? (int64_t)fl : (int64_t)lim;
+    if (draw2(a.seed, (uint32_t)p, a.step, pic::kTagInj, 0).a < N - fl) ++k;
+    a.cnt[p] = (uint32_t)(k < (int64_t)a.cap0 + 1 ? k : (int64_t)a.cap0 + 1);
+}
+
+// one block per patch, its electrons in order
+__global__ __launch_bounds__(kBlock) void k_emit_place(EmitArgs a) {
+    const int64_t p = blockIdx.x;
+    if (p >= a.npatch || a.st->skip) return;
+    const uint32_t k = a.cnt[p];
+    for (uint32_t j = threadIdx.x; j < k; j += blockDim.x) {
+        const double ua = draw2(a.seed, (uint32_t)p, a.step, pic::kTagInj, 1u + j).a;
+        double q[5];
+        ring_point(a, p, ua, q);
+        const uint64_t o = a.offs[p] + j;
+        const uint64_t s = a.st->base_n[0] + o;
+        a.r[s] = q[0] + 1e-3 * q[2];
+        a.z[s] = q[1] + 1e-3 * q[3];
+        a.vr[s] = 0.0;
+        a.vt[s] = 0.0;
+        a.vz[s] = 0.0;
+        a.id[s] = (uint32_t)(a.st->base_id + o);
+    }
+}
+
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// scratch: State, CG vectors r, p, q, partials (4 * kCgBlocks), counters (8)
-size_t layout(const pic_rz_config* c, char* base, State** st, double** r, double** p, double** q, double** part,
-              unsigned long long** cnt) {
+int64_t patches(const pic_rz_config* c) {
+    if (c->fn_rings <= 0) return 0;
+    const double zc = (c->tip_h - c->tip_r) / c->h;
+    return (int64_t)c->fn_rings + (zc > 0.0 ? (int64_t)std::ceil(zc) : 0);
+}
+
+// work memory carved from the scratch buffer
+struct Work {
+    State* st = nullptr;
+    double *r = nullptr, *p = nullptr, *q = nullptr, *part = nullptr;  // CG
+    unsigned long long* cnt = nullptr;                                   // moments counters (8)
+    uint32_t *ccnt = nullptr, *fill = nullptr, *start = nullptr;         // 3 nc each
+    uint32_t *seg = nullptr, *sorted = nullptr;                          // sum of caps each
+    int32_t* cellof = nullptr;
+    uint8_t* used = nullptr;
+    uint8_t* pflag = nullptr;  // cap[2]
+    double* ve = nullptr;      // 3 cap[2]
+    uint32_t *bcnt = nullptr, *bpre = nullptr;  // 2 nblk each
+    uint32_t* pcnt = nullptr;                   // patches
+    uint64_t* poff = nullptr;
+};
+
+size_t layout(const pic_rz_config* c, const int64_t cap[3], char* base, Work* w) {
     const size_t nn = (size_t)c->nr * c->nz;
+    const size_t nc = (size_t)(c->nr - 1) * (c->nz - 1);
+    const size_t ncap = (size_t)(cap[0] + cap[1] + cap[2]);
+    const size_t nblk = (size_t)((cap[2] + kBlock - 1) / kBlock);
+    const size_t np = (size_t)patches(c);
     size_t off = 0;
     auto take = [&](size_t b) -> char* {
         char* x = base ? base + off : nullptr;
         off = align256(off + b);
         return x;
     };
-    char* a = take(sizeof(State));
-    char* b = take(nn * 8);
-    char* d = take(nn * 8);
-    char* e = take(nn * 8);
-    char* f = take(4 * kCgBlocks * 8);
-    char* g = take(8 * 8);
-    if (st) *st = (State*)a;
-    if (r) *r = (double*)b;
-    if (p) *p = (double*)d;
-    if (q) *q = (double*)e;
-    if (part) *part = (double*)f;
-    if (cnt) *cnt = (unsigned long long*)g;
+    Work t;
+    t.st = (State*)take(sizeof(State));
+    t.r = (double*)take(nn * 8);
+    t.p = (double*)take(nn * 8);
+    t.q = (double*)take(nn * 8);
+    t.part = (double*)take(4 * kCgBlocks * 8);
+    t.cnt = (unsigned long long*)take(8 * 8);
+    t.ccnt = (uint32_t*)take(6 * nc * 4);  // counts, then the placement counters
+    t.fill = t.ccnt ? t.ccnt + 3 * nc : nullptr;
+    t.start = (uint32_t*)take(3 * nc * 4);
+    t.seg = (uint32_t*)take(ncap * 4);
+    t.sorted = (uint32_t*)take(ncap * 4);
+    t.cellof = (int32_t*)take(ncap * 4);
+    t.used = (uint8_t*)take(ncap);
+    t.pflag = (uint8_t*)take((size_t)cap[2]);
+    t.ve = (double*)take((size_t)cap[2] * 24);
+    t.bcnt = (uint32_t*)take(2 * nblk * 4);
+    t.bpre = (uint32_t*)take(2 * nblk * 4);
+    t.pcnt = (uint32_t*)take(np * 4 + 4);
+    t.poff = (uint64_t*)take(np * 8 + 8);
+    if (w) *w = t;
     return off + 256;
 }
 
@@ -372,7 +880,18 @@ const char* check(const pic_rz_config* c) {
         return "the tip does not fit in the box with two spacings to spare";
     if (!(c->m_ion > 0)) return "m_ion must be positive";
     if (!(c->laplace_rtol > 0) || !(c->step_rtol > 0) || c->maxit < 1) return "need positive tolerances and maxit";
+    if (c->xs_n < 0 || c->xs_n == 1) return "xs_n must be 0 or >= 2";
+    if (c->xs_n > 0 && !(c->xs_emin > 0 && c->xs_emax > c->xs_emin && c->xi > 0))
+        return "collisions need 0 < xs_emin < xs_emax and xi > 0";
+    if (c->fn_rings < 0 || c->fn_rings > (1 << 20)) return "fn_rings out of range";
+    if (c->fn_rings > 0 && !(c->phi_w > 0 && c->tip_r > 0)) return "emission needs phi_w > 0 and a tip";
     return nullptr;
+}
+
+bool caps_ok(const int64_t cap[3]) {
+    for (int s = 0; s < 3; ++s)
+        if (cap[s] < 0 || cap[s] >= ((int64_t)1 << 31)) return false;
+    return cap[0] + cap[1] + cap[2] < ((int64_t)1 << 32);
 }
 
 }  // namespace pic_rz
@@ -382,6 +901,7 @@ struct pic_rz_ctx {
     pic_rz_buffers buf;
     hipStream_t stream = nullptr;
     pic_rz::Geo g;
+    pic_rz::Work w;
     pic_rz::State* st = nullptr;
     double *r = nullptr, *p = nullptr, *q = nullptr, *part = nullptr;
     unsigned long long* cnt = nullptr;
@@ -461,13 +981,124 @@ pic_status field(pic_rz_ctx* c) {
     return hip_ok(c, hipGetLastError(), "field");
 }
 
+CollArgs coll_args(pic_rz_ctx* c, uint32_t step) {
+    CollArgs a{};
+    a.g = c->g;
+    a.nc = (int64_t)(c->g.nr - 1) * (c->g.nz - 1);
+    int64_t off = 0;
+    for (int s = 0; s < 3; ++s) {
+        a.r[s] = c->buf.r[s];
+        a.z[s] = c->buf.z[s];
+        a.vr[s] = c->buf.vr[s];
+        a.vt[s] = c->buf.vt[s];
+        a.vz[s] = c->buf.vz[s];
+        a.id[s] = c->buf.id[s];
+        a.cap[s] = c->buf.cap[s];
+        a.off[s] = off;
+        off += c->buf.cap[s];
+    }
+    a.st = c->st;
+    a.cnt = c->w.ccnt;
+    a.fill = c->w.fill;
+    a.start = c->w.start;
+    a.seg = c->w.seg;
+    a.sorted = c->w.sorted;
+    a.cellof = c->w.cellof;
+    a.used = c->w.used;
+    a.pflag = c->w.pflag;
+    a.ve = c->w.ve;
+    a.bcnt = c->w.bcnt;
+    a.bpre = c->w.bpre;
+    a.nblk = (c->buf.cap[2] + kBlock - 1) / kBlock;
+    a.E = c->buf.field;
+    a.xs = c->buf.xs;
+    a.xs_n = c->cfg.xs_n;
+    a.xs_emin = c->cfg.xs_emin;
+    a.xs_lnr = std::log(c->cfg.xs_emax / c->cfg.xs_emin);
+    a.h = c->cfg.h;
+    a.dt = c->cfg.dt;
+    a.m_ion = c->cfg.m_ion;
+    a.xi = c->cfg.xi;
+    a.seed = c->cfg.seed;
+    a.step = step;
+    // Eq. dfi: w(E) = adk_c (20.5 xi^1.5 / E)^(2 n - 1) exp(-6.83 xi^1.5 / E) per fs
+    const double n = 3.69 / std::sqrt(c->cfg.xi);
+    a.adk_c = 1.52 * std::pow(4.0, n) * c->cfg.xi / (n * std::tgamma(2.0 * n));
+    a.adk_e = 2.0 * n - 1.0;
+    a.x32 = std::pow(c->cfg.xi, 1.5);
+    a.dt_fs = c->cfg.dt * 1e15;
+    a.ebsi = 1.5 * a.x32;
+    return a;
+}
+
+// (e, Cu) pairs, (Cu+, Cu) pairs, field ionization, then the products
+void collide(pic_rz_ctx* c, uint32_t step) {
+    CollArgs a = coll_args(c, step);
+    const int64_t ncap = c->buf.cap[0] + c->buf.cap[1] + c->buf.cap[2];
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid_of(6 * a.nc)), dim3(kBlock), 0, c->stream, a.cnt, 6 * a.nc);
+    for (int s = 0; s < 3; ++s)
+        if (c->buf.cap[s] > 0)
+            hipLaunchKernelGGL(k_cells, dim3(grid_of(c->buf.cap[s])), dim3(kBlock), 0, c->stream, a, s);
+    hipLaunchKernelGGL(k_scan<uint32_t>, dim3(1), dim3(kScanBlock), 0, c->stream, (const uint32_t*)a.cnt, a.start,
+                       3 * a.nc, c->st);
+    for (int s = 0; s < 3; ++s)
+        if (c->buf.cap[s] > 0)
+            hipLaunchKernelGGL(k_place, dim3(grid_of(c->buf.cap[s])), dim3(kBlock), 0, c->stream, a, s);
+    hipLaunchKernelGGL(k_rank, dim3(grid_of(ncap)), dim3(kBlock), 0, c->stream, a);
+    if (c->buf.cap[0] > 0)
+        hipLaunchKernelGGL(k_pair, dim3(grid_of(c->buf.cap[0])), dim3(kBlock), 0, c->stream, a, 1);
+    if (c->buf.cap[1] > 0)
+        hipLaunchKernelGGL(k_pair, dim3(grid_of(c->buf.cap[1])), dim3(kBlock), 0, c->stream, a, 2);
+    if (c->buf.cap[2] == 0) return;
+    hipLaunchKernelGGL(k_fi, dim3(grid_of(c->buf.cap[2])), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(k_prod_count, dim3((unsigned)a.nblk), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(k_scan<uint32_t>, dim3(1), dim3(kScanBlock), 0, c->stream, (const uint32_t*)a.bcnt, a.bpre,
+                       2 * a.nblk, c->st);
+    hipLaunchKernelGGL(k_commit, dim3(1), dim3(64), 0, c->stream, c->st, 0, c->buf.cap[0], c->buf.cap[1]);
+    hipLaunchKernelGGL(k_prod_place, dim3((unsigned)a.nblk), dim3(kBlock), 0, c->stream, a);
+}
+
+// Fowler-Nordheim emission from the rings of the tip
+void emit(pic_rz_ctx* c, uint32_t step) {
+    EmitArgs a{};
+    a.g = c->g;
+    a.phi = c->buf.phi;
+    a.rings = c->cfg.fn_rings;
+    a.npatch = patches(&c->cfg);
+    a.h = c->cfg.h;
+    a.dt = c->cfg.dt;
+    a.phi_w = c->cfg.phi_w;
+    a.phi_w15 = std::pow(c->cfg.phi_w, 1.5);
+    a.fn_a = kQe * kQe / (8.0 * kPi * pic::kHpl);
+    a.fn_b = (8.0 * kPi / 3.0) * std::sqrt(2.0 * kMe) / (kQe * pic::kHpl) * std::pow(kQe, 1.5);
+    a.fn_cs2 = kQe / (4.0 * kPi * kEps0);
+    a.seed = c->cfg.seed;
+    a.step = step;
+    a.cap0 = c->buf.cap[0];
+    a.cnt = c->w.pcnt;
+    a.offs = c->w.poff;
+    a.r = c->buf.r[0];
+    a.z = c->buf.z[0];
+    a.vr = c->buf.vr[0];
+    a.vt = c->buf.vt[0];
+    a.vz = c->buf.vz[0];
+    a.id = c->buf.id[0];
+    a.st = c->st;
+    if (a.npatch == 0) return;
+    hipLaunchKernelGGL(k_emit_count, dim3(grid_of(a.npatch)), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(k_scan<uint64_t>, dim3(1), dim3(kScanBlock), 0, c->stream, (const uint32_t*)a.cnt, a.offs,
+                       a.npatch, c->st);
+    hipLaunchKernelGGL(k_commit, dim3(1), dim3(64), 0, c->stream, c->st, 1, c->buf.cap[0], c->buf.cap[1]);
+    hipLaunchKernelGGL(k_emit_place, dim3((unsigned)a.npatch), dim3(kBlock), 0, c->stream, a);
+}
+
 }  // namespace
 
 extern "C" {
 
 pic_status pic_rz_scratch_size(const pic_rz_config* cfg, const int64_t cap[3], size_t* bytes) {
-    if (check(cfg) || !cap || !bytes) return PIC_E_INVALID_ARG;
-    *bytes = layout(cfg, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    if (check(cfg) || !cap || !bytes || !caps_ok(cap)) return PIC_E_INVALID_ARG;
+    *bytes = layout(cfg, cap, nullptr, nullptr);
     return PIC_OK;
 }
 
@@ -477,8 +1108,9 @@ pic_status pic_rz_init(const pic_rz_config* cfg, const pic_rz_buffers* bufs, voi
     if (check(cfg) || !bufs) return PIC_E_INVALID_ARG;
     if (!bufs->phi || !bufs->phi1 || !bufs->rho || !bufs->field || !bufs->node_type || !bufs->scratch)
         return PIC_E_INVALID_ARG;
-    if (bufs->scratch_bytes < layout(cfg, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr))
+    if (!caps_ok(bufs->cap) || bufs->scratch_bytes < layout(cfg, bufs->cap, nullptr, nullptr))
         return PIC_E_INVALID_ARG;
+    if (cfg->xs_n > 0 && !bufs->xs) return PIC_E_INVALID_ARG;
     for (int s = 0; s < 3; ++s) {
         if (bufs->n[s] < 0 || bufs->n[s] > bufs->cap[s]) return PIC_E_INVALID_ARG;
         if (bufs->cap[s] > 0 && (!bufs->r[s] || !bufs->z[s] || !bufs->vr[s] || !bufs->vt[s] || !bufs->vz[s] ||
@@ -495,9 +1127,37 @@ pic_status pic_rz_init(const pic_rz_config* cfg, const pic_rz_buffers* bufs, voi
     c->g.H = cfg->tip_h / cfg->h;
     // 256-byte alignment of the work memory
     char* base = (char*)(((uintptr_t)bufs->scratch + 255) & ~(uintptr_t)255);
-    layout(cfg, base, &c->st, &c->r, &c->p, &c->q, &c->part, &c->cnt);
+    layout(cfg, bufs->cap, base, &c->w);
+    c->st = c->w.st;
+    c->r = c->w.r;
+    c->p = c->w.p;
+    c->q = c->w.q;
+    c->part = c->w.part;
+    c->cnt = c->w.cnt;
     const int64_t nn = (int64_t)cfg->nr * cfg->nz;
-    pic_status s = hip_ok(c, hipMemsetAsync(c->st, 0, sizeof(State), c->stream), "zero");
+    State h0{};
+    for (int s = 0; s < 3; ++s) h0.n[s] = (unsigned long long)bufs->n[s];
+    pic_status s = hip_ok(c, hipMemcpyAsync(c->st, &h0, sizeof(State), hipMemcpyHostToDevice, c->stream), "copy");
+    for (int sp = 0; sp < 3 && s == PIC_OK; ++sp)
+        if (bufs->n[sp] > 0)
+            hipLaunchKernelGGL(k_check_ids, dim3(grid_of(bufs->n[sp])), dim3(kBlock), 0, c->stream, bufs->id[sp],
+                               bufs->n[sp], c->st);
+    if (s == PIC_OK) {
+        State h1{};
+        s = hip_ok(c, hipMemcpyAsync(&h1, c->st, sizeof(State), hipMemcpyDeviceToHost, c->stream), "copy");
+        if (s == PIC_OK) s = hip_ok(c, hipStreamSynchronize(c->stream), "sync");
+        if (s == PIC_OK && h1.skip) {
+            delete c;
+            return PIC_E_INVALID_ARG;
+        }
+        if (s == PIC_OK) {
+            // every species' ids continue from the largest of all
+            State h2 = h1;
+            h2.skip = 0;
+            s = hip_ok(c, hipMemcpyAsync(c->st, &h2, sizeof(State), hipMemcpyHostToDevice, c->stream), "copy");
+            if (s == PIC_OK) s = hip_ok(c, hipStreamSynchronize(c->stream), "sync");
+        }
+    }
     if (s == PIC_OK) {
         hipLaunchKernelGGL(k_types, dim3(grid_of(nn)), dim3(kBlock), 0, c->stream, c->g, bufs->node_type);
         s = hip_ok(c, hipMemsetAsync(bufs->phi1, 0, nn * 8, c->stream), "zero");
@@ -549,11 +1209,16 @@ pic_status pic_rz_solve(pic_rz_ctx* c, double rtol, int32_t maxit, pic_solve_inf
 
 pic_status pic_rz_step(pic_rz_ctx* c, int32_t nsteps, uint32_t flags) {
     if (!c || nsteps < 0) return PIC_E_INVALID_ARG;
+    if ((flags & PIC_RZ_COLLIDE) && c->cfg.xs_n == 0) return fail(c, PIC_E_INVALID_ARG, "collisions need tables");
+    if ((flags & PIC_RZ_EMIT) && c->cfg.fn_rings == 0) return fail(c, PIC_E_INVALID_ARG, "emission needs rings");
     const double qm[3] = {-kQe / kMe, kQe / c->cfg.m_ion, 0.0};
+    const int64_t* cap = c->buf.cap;
     for (int t = 0; t < nsteps; ++t) {
+        const uint32_t step = (uint32_t)c->step;
+        if (flags & PIC_RZ_EMIT) emit(c, step);
         if (flags & PIC_RZ_PUSH) {
             for (int s = 0; s < 3; ++s) {
-                if (c->buf.n[s] == 0) continue;
+                if (cap[s] == 0) continue;
                 PushArgs a;
                 a.g = c->g;
                 a.r = c->buf.r[s];
@@ -562,22 +1227,22 @@ pic_status pic_rz_step(pic_rz_ctx* c, int32_t nsteps, uint32_t flags) {
                 a.vt = c->buf.vt[s];
                 a.vz = c->buf.vz[s];
                 a.id = c->buf.id[s];
-                a.n = c->buf.n[s];
                 a.E = c->buf.field;
                 a.kq = qm[s] * c->cfg.dt * c->cfg.dt / c->cfg.h;
                 a.sp = s;
                 a.st = c->st;
-                hipLaunchKernelGGL(k_push, dim3(grid_of(a.n)), dim3(kBlock), 0, c->stream, a);
+                hipLaunchKernelGGL(k_push, dim3(grid_of(cap[s])), dim3(kBlock), 0, c->stream, a);
             }
         }
+        if (flags & PIC_RZ_COLLIDE) collide(c, step);
         if (flags & PIC_RZ_DEPOSIT) {
             const int64_t nn = (int64_t)c->g.nr * c->g.nz;
             hipLaunchKernelGGL(k_zero_rho, dim3(grid_of(nn)), dim3(kBlock), 0, c->stream, c->buf.rho, nn);
             for (int s = 0; s < 2; ++s)
-                if (c->buf.n[s] > 0)
-                    hipLaunchKernelGGL(k_deposit, dim3(grid_of(c->buf.n[s])), dim3(kBlock), 0, c->stream, c->g,
-                                       c->buf.r[s], c->buf.z[s], c->buf.id[s], c->buf.n[s], s == 0 ? -1 : 1,
-                                       c->buf.rho);
+                if (cap[s] > 0)
+                    hipLaunchKernelGGL(k_deposit, dim3(grid_of(cap[s])), dim3(kBlock), 0, c->stream, c->g,
+                                       c->buf.r[s], c->buf.z[s], c->buf.id[s], (const State*)c->st, s,
+                                       (int64_t)(s == 0 ? -1 : 1), c->buf.rho);
         }
         pic_status st = hip_ok(c, hipGetLastError(), "step");
         if (st != PIC_OK) return st;
@@ -590,6 +1255,16 @@ pic_status pic_rz_step(pic_rz_ctx* c, int32_t nsteps, uint32_t flags) {
         }
         if (flags & PIC_RZ_ADVANCE) c->step++;
     }
+    if (flags & (PIC_RZ_EMIT | PIC_RZ_COLLIDE)) {
+        int err = 0;
+        pic_status s = hip_ok(c, hipMemcpyAsync(&err, &c->st->error, sizeof(int), hipMemcpyDeviceToHost, c->stream),
+                              "copy");
+        if (s == PIC_OK) s = hip_ok(c, hipStreamSynchronize(c->stream), "sync");
+        if (s != PIC_OK) return s;
+        if (err != 0)
+            return fail(c, (pic_status)err, err == PIC_E_CAPACITY ? "new particles exceed a species' capacity"
+                                                                  : "particle ids exhausted");
+    }
     return PIC_OK;
 }
 
@@ -598,9 +1273,9 @@ pic_status pic_rz_moments(pic_rz_ctx* c, pic_rz_moments_t* out) {
     pic_status s = hip_ok(c, hipMemsetAsync(c->cnt, 0, 8 * 8, c->stream), "zero");
     if (s != PIC_OK) return s;
     for (int sp = 0; sp < 3; ++sp)
-        if (c->buf.n[sp] > 0)
-            hipLaunchKernelGGL(k_counts, dim3(grid_of(c->buf.n[sp])), dim3(kBlock), 0, c->stream, c->buf.id[sp],
-                               c->buf.n[sp], c->cnt + sp);
+        if (c->buf.cap[sp] > 0)
+            hipLaunchKernelGGL(k_counts, dim3(grid_of(c->buf.cap[sp])), dim3(kBlock), 0, c->stream, c->buf.id[sp],
+                               (const State*)c->st, sp, c->cnt + sp);
     const int64_t nn = (int64_t)c->g.nr * c->g.nz;
     hipLaunchKernelGGL(k_qsum, dim3(256), dim3(kBlock), 0, c->stream, c->buf.rho, nn, c->cnt + 3);
     unsigned long long h[8];
@@ -620,6 +1295,10 @@ pic_status pic_rz_moments(pic_rz_ctx* c, pic_rz_moments_t* out) {
     out->apex_field1 = c->F1;
     out->last_cg_iters = c->last_iters;
     out->error = st.error;
+    for (int sp = 0; sp < 3; ++sp) out->n_slots[sp] = (int64_t)st.n[sp];
+    for (int k = 0; k < 5; ++k) out->events[k] = (int64_t)st.events[k];
+    out->injected = (int64_t)st.injected;
+    out->next_id = (int64_t)st.next_id;
     return PIC_OK;
 }
 

@@ -13,27 +13,31 @@ import torch
 from .pic import DEAD, PIC_OK, PicError, lib as _pic_lib, pic_solve_info
 
 PIC_RZ_PUSH, PIC_RZ_DEPOSIT, PIC_RZ_SOLVE, PIC_RZ_ADVANCE, PIC_RZ_FIELD = 1, 2, 4, 8, 16
+PIC_RZ_EMIT, PIC_RZ_COLLIDE = 32, 64
 PIC_RZ_FULL = 15
+PIC_RZ_ALL = 111
 
 
 class pic_rz_config(C.Structure):
     _fields_ = [("nr", C.c_int32), ("nz", C.c_int32), ("h", C.c_double), ("tip_r", C.c_double),
                 ("tip_h", C.c_double), ("apex_field", C.c_double), ("dt", C.c_double), ("m_ion", C.c_double),
                 ("laplace_rtol", C.c_double), ("maxit", C.c_int32), ("reserved", C.c_int32),
-                ("step_rtol", C.c_double)]
+                ("step_rtol", C.c_double), ("seed", C.c_uint64), ("xi", C.c_double), ("phi_w", C.c_double),
+                ("xs_emin", C.c_double), ("xs_emax", C.c_double), ("xs_n", C.c_int32), ("fn_rings", C.c_int32)]
 
 
 class pic_rz_buffers(C.Structure):
     _fields_ = [(k, C.c_void_p * 3) for k in ("r", "z", "vr", "vt", "vz", "id")] + \
                [("cap", C.c_int64 * 3), ("n", C.c_int64 * 3), ("phi", C.c_void_p), ("phi1", C.c_void_p),
                 ("rho", C.c_void_p), ("field", C.c_void_p), ("node_type", C.c_void_p), ("scratch", C.c_void_p),
-                ("scratch_bytes", C.c_size_t)]
+                ("scratch_bytes", C.c_size_t), ("xs", C.c_void_p)]
 
 
 class pic_rz_moments_t(C.Structure):
     _fields_ = [("n_alive", C.c_int64 * 3), ("absorbed", (C.c_int64 * 5) * 3), ("q_total", C.c_int64),
                 ("step", C.c_int64), ("v0", C.c_double), ("apex_field1", C.c_double),
-                ("last_cg_iters", C.c_int32), ("error", C.c_int32)]
+                ("last_cg_iters", C.c_int32), ("error", C.c_int32), ("n_slots", C.c_int64 * 3),
+                ("events", C.c_int64 * 5), ("injected", C.c_int64), ("next_id", C.c_int64)]
 
 
 _bound = False
@@ -92,24 +96,35 @@ def pic_rz_moments(ctx) -> dict:
     _check(lib().pic_rz_moments(ctx, C.byref(m)), ctx)
     return {"n_alive": np.array(m.n_alive[:]), "absorbed": np.array([list(r) for r in m.absorbed]),
             "q_total": m.q_total, "step": m.step, "v0": m.v0, "apex_field1": m.apex_field1,
-            "last_cg_iters": m.last_cg_iters, "error": m.error}
+            "last_cg_iters": m.last_cg_iters, "error": m.error, "n_slots": np.array(m.n_slots[:]),
+            "events": np.array(m.events[:]), "injected": m.injected, "next_id": m.next_id}
 
 
 class RZSimulation:
     """One axisymmetric instance on a GPU. load: dict species index ->
     dict r, z, vr, vt, vz (grid units, FP64); particles are numbered in load
-    order (species 0, 1, 2)."""
+    order (species 0, 1, 2) unless ids (species -> uint32 array) is given.
+    xs: (emin, emax, elastic, ionization, charge exchange) cross-section
+    tables for the collisions; fn_rings > 0 enables the emission."""
 
     def __init__(self, nr, nz, h, tip_r, tip_h, apex_field, dt, m_ion, load, caps=None, laplace_rtol=1e-13,
-                 step_rtol=1e-10, maxit=100000, device="cuda"):
+                 step_rtol=1e-10, maxit=100000, device="cuda", seed=1, xs=None, xi=7.726380, phi_w=4.5,
+                 fn_rings=0, ids=None):
         self.device = torch.device(device)
         self.cfg = pic_rz_config(nr=nr, nz=nz, h=h, tip_r=tip_r, tip_h=tip_h, apex_field=apex_field, dt=dt,
-                                 m_ion=m_ion, laplace_rtol=laplace_rtol, maxit=maxit, step_rtol=step_rtol)
+                                 m_ion=m_ion, laplace_rtol=laplace_rtol, maxit=maxit, step_rtol=step_rtol,
+                                 seed=seed, xi=xi, phi_w=phi_w, fn_rings=fn_rings)
+        self.xs = None
+        if xs is not None:
+            self.cfg.xs_emin, self.cfg.xs_emax = xs[0], xs[1]
+            self.cfg.xs_n = len(xs[2])
+            self.xs = torch.as_tensor(np.concatenate([np.asarray(t, np.float64) for t in xs[2:5]])).to(self.device)
         n = [len(load[s]["r"]) if s in load else 0 for s in range(3)]
         caps = caps or [max(k, 1) for k in n]
         self.sp = []
         b = pic_rz_buffers()
         nid = 0
+        ids_given = ids
         for s in range(3):
             d = {}
             for k in ("r", "z", "vr", "vt", "vz"):
@@ -119,7 +134,9 @@ class RZSimulation:
                 d[k] = t
                 getattr(b, k)[s] = t.data_ptr()
             ids = torch.full((caps[s],), -1, dtype=torch.int32, device=self.device)
-            if n[s]:
+            if n[s] and ids_given is not None:
+                ids[: n[s]] = torch.as_tensor(np.asarray(ids_given[s], np.uint32).view(np.int32))
+            elif n[s]:
                 ids[: n[s]] = torch.arange(nid, nid + n[s], dtype=torch.int32)
             nid += n[s]
             d["id"] = ids
@@ -138,6 +155,7 @@ class RZSimulation:
         for k in ("phi", "phi1", "rho", "field", "node_type", "scratch"):
             setattr(b, k, getattr(self, k).data_ptr())
         b.scratch_bytes = sb + 256
+        b.xs = self.xs.data_ptr() if self.xs is not None else None
         self.bufs = b
         self.n = n
         torch.cuda.synchronize(self.device)
@@ -153,12 +171,13 @@ class RZSimulation:
         return pic_rz_moments(self.ctx)
 
     def state(self):
-        torch.cuda.synchronize(self.device)
+        """Alive particles of each species in slot order (= id order)."""
+        n = self.moments()["n_slots"]
         out = []
         for s in range(3):
-            ids = self.sp[s]["id"][: self.n[s]].cpu().numpy().view(np.uint32)
+            ids = self.sp[s]["id"][: n[s]].cpu().numpy().view(np.uint32)
             alive = ids != DEAD
-            d = {k: self.sp[s][k][: self.n[s]].cpu().numpy()[alive] for k in ("r", "z", "vr", "vt", "vz")}
+            d = {k: self.sp[s][k][: n[s]].cpu().numpy()[alive] for k in ("r", "z", "vr", "vt", "vz")}
             d["id"] = ids[alive]
             out.append(d)
         return out

@@ -130,3 +130,138 @@ def test_rz_whole_steps():
     m = g.moments()
     print("alive", m["n_alive"], "absorbed", m["absorbed"].sum(axis=1), "CG", m["last_cg_iters"], flush=True)
     assert np.array_equal(m["absorbed"], o.absorbed)
+
+
+# -- collisions, field ionization, emission -----------------------------------
+from paper_2402_08404_amd import workloads as W  # noqa: E402
+
+
+def _tables(scale=1e4):
+    el, iz, cx = W.synthetic_tables()
+    return (1e-2, 1e4, el * scale, iz * scale, cx * scale)
+
+
+def _pair_all(seed=1, n=(3000, 1500, 6000), apex=10e9, xs=True, fn_rings=0, caps=None, load=None):
+    geom = dict(GEOM, apex_field=apex)
+    tabs = _tables() if xs else None
+    o = RZ(geom["nr"], geom["nz"], geom["h"], geom["tip_r"], geom["tip_h"], geom["apex_field"], geom["dt"],
+           geom["m_ion"], seed=seed, xs=tabs, fn_rings=fn_rings or 16)
+    if load is None:
+        load = _load(o, np.random.default_rng(seed), n)
+    nid = 0
+    for s in range(3):
+        m = len(load[s]["r"]) if s in load else 0
+        if m:
+            o.load(s, load[s], np.arange(nid, nid + m))
+        nid += m
+    if caps is None:
+        cnt = [len(load[s]["r"]) if s in load else 0 for s in range(3)]
+        caps = [cnt[0] + cnt[2] + 4096, cnt[1] + cnt[2] + 1, cnt[2] + 1]
+    g = rz.RZSimulation(**geom, load=load, laplace_rtol=1e-13, step_rtol=1e-14, seed=seed, xs=tabs,
+                        fn_rings=fn_rings, caps=caps)
+    g.set_phi(o.phi)
+    return g, o
+
+
+def _compare_all(g, o, tol):
+    gs = g.state()
+    for s in range(3):
+        b = o.sp[s]
+        a = gs[s]
+        if b is None:
+            assert len(a["id"]) == 0
+            continue
+        assert np.array_equal(a["id"], b["id"]), (s, len(a["id"]), len(b["id"]))
+        for k in ("r", "z", "vr", "vt", "vz"):
+            d = np.abs(a[k] - b[k])
+            scale = np.abs(b[k]) + 1e-3 * (np.abs(b[k]).max() if len(b[k]) else 0.0) + 1e-300
+            assert (d <= tol * scale).all(), (s, k, (d / scale).max())
+
+
+def test_rz_collide_parity():
+    """Four collision stages (no push): the same pairs, events, velocities
+    and products by id; ids in slot order."""
+    print("case: rz collide, seed 21", flush=True)
+    g, o = _pair_all(seed=21)
+    for step in range(4):
+        g.step(1, rz.PIC_RZ_COLLIDE | rz.PIC_RZ_ADVANCE)
+        o.collide()
+        o.step_no += 1
+        _compare_all(g, o, 1e-12)
+        m = g.moments()
+        assert np.array_equal(m["events"], o.events), (m["events"], o.events)
+        assert m["next_id"] == o.next_id
+    assert o.events[1] > 50 and o.events[2] > 20 and o.events[3] > 20, o.events
+
+
+def test_rz_field_ionization_parity():
+    """Neutrals on a shell around the apex at 25 GV/m: the same neutrals
+    ionize, with the same products."""
+    print("case: rz field ionization", flush=True)
+    rng = np.random.default_rng(5)
+    o0 = RZ(GEOM["nr"], GEOM["nz"], GEOM["h"], GEOM["tip_r"], GEOM["tip_h"], 25e9, GEOM["dt"], GEOM["m_ion"])
+    n = 6000
+    th = rng.uniform(0, 0.5 * math.pi, n)
+    rad = o0.R + rng.uniform(0.3, 3.0, n)
+    zc = o0.H - o0.R
+    load = {0: {k: np.zeros(0) for k in ("r", "z", "vr", "vt", "vz")},
+            1: {k: np.zeros(0) for k in ("r", "z", "vr", "vt", "vz")},
+            2: {"r": rad * np.sin(th), "z": zc + rad * np.cos(th), "vr": rng.normal(0, 1e-3, n),
+                "vt": rng.normal(0, 1e-3, n), "vz": rng.normal(0, 1e-3, n)}}
+    g, o = _pair_all(seed=9, apex=25e9, load=load, caps=[n, n, n])
+    for step in range(3):
+        g.step(1, rz.PIC_RZ_COLLIDE | rz.PIC_RZ_ADVANCE)
+        o.collide()
+        o.step_no += 1
+        _compare_all(g, o, 1e-14)
+    m = g.moments()
+    assert np.array_equal(m["events"], o.events)
+    assert o.events[4] > 40, o.events
+
+
+def test_rz_emission_parity():
+    print("case: rz emission", flush=True)
+    load = {s: {k: np.zeros(0) for k in ("r", "z", "vr", "vt", "vz")} for s in range(3)}
+    g, o = _pair_all(seed=3, apex=20e9, load=load, fn_rings=16, caps=[4096, 16, 16], xs=False)
+    for step in range(20):
+        g.step(1, rz.PIC_RZ_EMIT | rz.PIC_RZ_ADVANCE)
+        o.emit()
+        o.step_no += 1
+    _compare_all(g, o, 1e-14)
+    m = g.moments()
+    assert m["injected"] == o.injected > 20, (m["injected"], o.injected)
+
+
+def test_rz_all_stages_steps():
+    """Ten whole steps with emission, push, collisions, deposit and solve:
+    the charge bit-exact, particles and events as the oracle's."""
+    print("case: rz all stages", flush=True)
+    g, o = _pair_all(seed=31, n=(4000, 1500, 8000), apex=14e9, fn_rings=16, caps=[40000, 20000, 8000])
+    g.step(1, rz.PIC_RZ_DEPOSIT | rz.PIC_RZ_SOLVE)
+    o.deposit()
+    o.solve()
+    for s in range(10):
+        g.step(1, rz.PIC_RZ_ALL)
+        o.step(emit=True, collide=True)
+        assert np.array_equal(g.grid("rho"), o.Q)
+        _compare_all(g, o, 1e-9)
+    m = g.moments()
+    print("events", m["events"], "injected", m["injected"], "alive", m["n_alive"], flush=True)
+    assert np.array_equal(m["events"], o.events)
+    assert np.array_equal(m["absorbed"], o.absorbed)
+    assert m["injected"] == o.injected
+
+
+def test_rz_capacity_and_ids():
+    print("case: rz capacity and ids", flush=True)
+    load = {s: {k: np.zeros(0) for k in ("r", "z", "vr", "vt", "vz")} for s in range(3)}
+    g, o = _pair_all(seed=3, apex=20e9, load=load, fn_rings=16, caps=[1, 1, 1], xs=False)
+    with pytest.raises(rz.PicError) as e:
+        g.step(5, rz.PIC_RZ_EMIT | rz.PIC_RZ_ADVANCE)
+    assert e.value.code == -3
+    assert g.moments()["n_slots"][0] <= 1
+    # initial ids must increase with the slot
+    ld = {2: {"r": np.array([10.0, 11.0]), "z": np.array([50.0, 50.0]), "vr": np.zeros(2), "vt": np.zeros(2),
+              "vz": np.zeros(2)}}
+    with pytest.raises(rz.PicError):
+        rz.RZSimulation(**GEOM, load=ld, ids={2: np.array([5, 4], np.uint32)})
