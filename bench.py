@@ -256,6 +256,10 @@ def main():
     ap.add_argument("--batch-compare", action="store_true",
                     help="with --batch: also time the same steps with the instances stepped one after another")
     ap.add_argument("--tuning", default=os.path.join(ROOT, "paper_2402_08404_amd", "tuning.json"))
+    ap.add_argument("--rz", action="store_true",
+                    help="the axisymmetric variant on the paper's geometry: every stage of its step")
+    ap.add_argument("--rz-scale", type=float, default=1.0, help="scale factor of the axisymmetric particle counts")
+    ap.add_argument("--rz-iters", action="store_true", help="with --rz: read the CG iterations after every step")
     ap.add_argument("--pmc-summary", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV",
                                                         "COPY_MIB"),
                     help="write the HBM traffic summary of rocprofv3 --pmc runs to profiles/ and exit")
@@ -279,7 +283,8 @@ def main():
         print(json.dumps(trace_summary(args.trace_summary), indent=1))
         return
     cpu_base = None
-    if not (args.no_cpu_baseline or args.calibrate_copy or args.batch or args.unet or args.learned_experiment):
+    if not (args.no_cpu_baseline or args.calibrate_copy or args.batch or args.unet or args.learned_experiment
+            or args.rz):
         print("[bench] cpu baseline (oracle processes)", file=sys.stderr, flush=True)
         cpu_base = cpu_baseline(args.workload, args.cpu_sample, args.cpu_steps, __import__("numpy"), args.cpu_procs)
     import torch
@@ -302,6 +307,8 @@ def main():
         return learned_experiment(args, log)
     if args.batch:
         return batch_main(args, log)
+    if args.rz:
+        return rz_main(args, log)
     if args.unet:
         return unet_main(args, log)
 
@@ -734,6 +741,102 @@ def batch_main(args, log):
         "serial_ms_per_step": serial,
     }
     b.close()
+    print(json.dumps(out), flush=True)
+
+
+def rz_cpu_baseline(geo, per_species, steps):
+    """The axisymmetric oracle on a bounded sample: per_species particles of
+    each species drawn like the GPU load, whole steps with every stage (its
+    solve is a direct sparse factorization of the same grid)."""
+    import numpy as np
+    from oracle.rz import RZ
+    from paper_2402_08404_amd import workloads as W
+    load = W.rz_load(geo, (per_species,) * 3, rng=np.random.default_rng(11))
+    o = RZ(geo["nr"], geo["nz"], geo["h"], geo["tip_r"], geo["tip_h"], geo["apex_field"], geo["dt"], geo["m_ion"],
+           seed=geo["seed"], xs=geo["xs"], fn_rings=geo["fn_rings"])
+    nid = 0
+    for s in range(3):
+        o.load(s, load[s], np.arange(nid, nid + per_species))
+        nid += per_species
+    t0 = time.perf_counter()
+    n = 0
+    for _ in range(steps):
+        n += sum(len(o.sp[s]["id"]) for s in range(3))
+        o.step(emit=True, collide=True)
+    wall = time.perf_counter() - t0
+    return {"value": n / wall, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{per_species} particles per species on the same grid, {steps} whole steps "
+                      f"({wall:.1f} s, one thread; the direct solve of the grid dominates)"}
+
+
+def rz_main(args, log):
+    """The axisymmetric variant on the paper's geometry: emission, push,
+    collisions, field ionization, deposit and the CG solve in every step."""
+    import numpy as np
+    import torch
+    from paper_2402_08404_amd import rz
+    from paper_2402_08404_amd import workloads as W
+    geo = W.rz_context()
+    counts = tuple(int(c * args.rz_scale) for c in (4_000_000, 4_000_000, 4_000_000))
+    t0 = time.perf_counter()
+    load = W.rz_load(geo, counts)
+    caps = [int(1.25 * counts[0]) + 65536, int(1.25 * counts[1]) + 4096, counts[2] + 1]
+    keys = ("nr", "nz", "h", "tip_r", "tip_h", "apex_field", "dt", "m_ion")
+    sim = rz.RZSimulation(**{k: geo[k] for k in keys}, load=load, caps=caps, step_rtol=1e-8, seed=geo["seed"],
+                          xs=geo["xs"], fn_rings=geo["fn_rings"])
+    del load
+    log(f"[bench] rz instance ready ({time.perf_counter() - t0:.1f} s), {sum(counts)} particles")
+    sim.step(1, rz.PIC_RZ_DEPOSIT | rz.PIC_RZ_SOLVE)
+    sim.step(args.warmup, rz.PIC_RZ_ALL)
+    m0 = sim.moments()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done, iters = 0, 0
+    while done < args.steps:
+        k = min(10, args.steps - done)
+        for _ in range(k):
+            sim.step(1, rz.PIC_RZ_ALL)
+            iters += sim.moments()["last_cg_iters"] if args.rz_iters else 0
+        done += k
+        log(f"[bench] rz step {done} ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    m1 = sim.moments()
+    n0, n1 = int(m0["n_alive"].sum()), int(m1["n_alive"].sum())
+    value = 0.5 * (n0 + n1) * args.steps / wall
+    # the push of every species, timed alone with HIP events on the library's
+    # stream: algorithmic bytes = 84 B per alive particle (r, z, vr, vt, vz
+    # and the id read, the five written) + the node field read once
+    nn = geo["nr"] * geo["nz"]
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    reps = 10
+    alive = int(sim.moments()["n_alive"].sum())
+    ev[0].record(stream)
+    for _ in range(reps):
+        sim.step(1, rz.PIC_RZ_PUSH)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    t_push = ev[0].elapsed_time(ev[1]) * 1e-3 / reps
+    push_bytes = 84.0 * alive + 16.0 * nn
+    ach = push_bytes / t_push / 1e9
+    cpu = None if args.no_cpu_baseline else rz_cpu_baseline(geo, 2000, 2)
+    out = {
+        "metric": "particle-steps/s (axisymmetric variant: emission, push, collisions, field ionization, "
+                  "deposit, CG solve)",
+        "value": float(value), "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "rz_context", "grid": [geo["nr"], geo["nz"]], "h_nm": geo["h"] * 1e9,
+                   "tip_r_nm": geo["tip_r"] * 1e9, "tip_h_um": geo["tip_h"] * 1e6, "particles": list(counts)},
+        "roofline": {"bound": "hbm", "kernel": "k_push (all species, one pass)", "achieved": ach, "peak": 8000.0,
+                     "unit": "GB/s", "frac": ach / 8000.0, "traffic": None,
+                     "launch_us": t_push * 1e6, "bytes": push_bytes},
+        "cpu_baseline": cpu,
+        "alive": [n0, n1], "events": m1["events"].tolist(), "injected": int(m1["injected"]),
+        "cg_iterations_per_step": (iters / args.steps) if args.rz_iters else None,
+    }
+    sim.close()
     print(json.dumps(out), flush=True)
 
 

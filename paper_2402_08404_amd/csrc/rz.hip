@@ -29,10 +29,13 @@ constexpr int kCgBlocks = 256;  // blocks of the CG kernels (one partial each, s
 constexpr uint8_t kFree = 0, kHeld0 = 1, kHeldV = 2;  // node types
 
 constexpr int kScanBlock = 1024;  // threads of the single-block scans
+constexpr int kRankSmall = 64;    // cells up to this many particles of a species: one rank per thread
+constexpr int kRankLds = 4096;    // up to this many: one block sorts the cell in LDS
+constexpr int kBigBlocks = 1024;  // blocks that take the larger cells in turn
 
 struct State {
     unsigned long long absorbed[3][5];
-    double rr, bb, pq, alpha, beta, rtol;
+    double rr, bb, pq, alpha, beta, rtol, rz;
     int it, maxit, done, error;
     unsigned long long n[3];       // slots in use per species
     unsigned long long next_id;    // id of the next new particle
@@ -41,7 +44,8 @@ struct State {
     unsigned long long base_n[2], base_id;  // first electron / ion slot and first id of the stage's new particles
     unsigned long long total;      // total of the last scan
     int skip;                      // the stage's new particles did not fit
-    int pad;
+    unsigned int nbig;             // (species, cell) keys above kRankSmall particles
+    unsigned long long ngrp[3];    // slots in use when the particles were grouped by cell
 };
 
 struct Geo {
@@ -95,7 +99,7 @@ struct CgArgs {
     const uint8_t* type;
     const int64_t* rho;
     double* phi;
-    double *r, *p, *q;
+    double *r, *p, *q, *z;  // z: the preconditioned residual
     double* part;  // 2 * kCgBlocks partials
     State* st;
     double qscale;  // 2^-40 e / (pi eps0 h)
@@ -123,8 +127,8 @@ __device__ inline void block_reduce2(double a, double b, double* part) {
     }
 }
 
-// phi at held nodes to their values; r = b - A phi and p = r on free nodes;
-// partials of r.r and of the right-hand side with the held values moved over
+// phi at held nodes to their values; r = b - A phi on free nodes; partials
+// of r.r and of the right-hand side with the held values moved over
 __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs a) {
     const int64_t nn = (int64_t)a.g.nr * a.g.nz;
     double rr = 0.0, bb = 0.0;
@@ -158,7 +162,6 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs a) {
         }
         const double r = b - ax;
         a.r[n] = r;
-        a.p[n] = r;
         rr += r * r;
         const double be = b + lift;
         bb += be * be;
@@ -206,7 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(CgArgs a) {
     if (threadIdx.x == 0) {
         double pq = 0.0;
         for (int b = 0; b < kCgBlocks; ++b) pq += a.part[2 * b];
-        alpha = a.st->rr / pq;
+        alpha = a.st->rz / pq;
     }
     __syncthreads();
     const int64_t nn = (int64_t)a.g.nr * a.g.nz;
@@ -221,17 +224,41 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(CgArgs a) {
     block_reduce2(rr, 0.0, a.part + 2 * kCgBlocks);
 }
 
-// (single block) beta, convergence
-__global__ void k_cg_scalars(CgArgs a) {
+// (single block) r.r from the partials, convergence
+__global__ void k_cg_check(CgArgs a) {
     if (threadIdx.x != 0) return;
     State* st = a.st;
     if (st->done) return;
     double rr = 0.0;
     for (int b = 0; b < kCgBlocks; ++b) rr += a.part[2 * kCgBlocks + 2 * b];
-    st->beta = rr / st->rr;
     st->rr = rr;
     st->it += 1;
     if (rr <= st->rtol * st->rtol * st->bb || st->it >= st->maxit) st->done = 1;
+}
+
+// partials of r.z; with first set, also p = z
+__global__ __launch_bounds__(kBlock) void k_pcg_rz(CgArgs a, int first) {
+    if (a.st->done) return;
+    const int64_t nn = (int64_t)a.g.nr * a.g.nz;
+    double rz = 0.0;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (int64_t)gridDim.x * blockDim.x) {
+        if (a.type[n] != kFree) continue;
+        const double z = a.z[n];
+        rz += a.r[n] * z;
+        if (first) a.p[n] = z;
+    }
+    block_reduce2(rz, 0.0, a.part);
+}
+
+// (single block) beta = r.z / previous r.z (first: only r.z)
+__global__ void k_pcg_beta(CgArgs a, int first) {
+    if (threadIdx.x != 0) return;
+    State* st = a.st;
+    if (st->done) return;
+    double rz = 0.0;
+    for (int b = 0; b < kCgBlocks; ++b) rz += a.part[2 * b];
+    st->beta = first ? 0.0 : rz / st->rz;
+    st->rz = rz;
 }
 
 __global__ __launch_bounds__(kBlock) void k_cg_p(CgArgs a) {
@@ -239,7 +266,160 @@ __global__ __launch_bounds__(kBlock) void k_cg_p(CgArgs a) {
     const double beta = a.st->beta;
     const int64_t nn = (int64_t)a.g.nr * a.g.nz;
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (int64_t)gridDim.x * blockDim.x)
-        if (a.type[n] == kFree) a.p[n] = a.r[n] + beta * a.p[n];
+        if (a.type[n] == kFree) a.p[n] = a.z[n] + beta * a.p[n];
+}
+
+// ---------------------------------------------------------------------------
+// Multigrid preconditioner of the CG: one V-cycle z = M r of the error
+// equation (held nodes at zero). Level l has nr_l x nz_l nodes; a dimension
+// is halved (node I of the coarse level at node 2 I of the finer) while its
+// cell count is even and at least 4; the coarse operator is the same finite
+// volume discretization at the coarse spacings H_r = 2^a h, H_z = 2^b h,
+// in units of pi eps0 h: radial couplings 2^b 2 (I -+ 1/2), axial couplings
+// 2^(2a-b) (r_hi^2 - r_lo^2) in coarse index units. A coarse node is held if
+// the finer node at its place is. Prolongation is bilinear, restriction its
+// transpose (the residual is an integrated charge, so it is summed). Damped
+// Jacobi (omega = 4/5) smooths, two sweeps before and two after; the coarsest
+// level, when it has at most kMgCoarseMax nodes, is swept kMgCoarseSweeps
+// times in LDS by one block (otherwise it is smoothed like the others). The
+// cycle is a fixed symmetric linear operator, as CG needs.
+constexpr int kMgMaxLevels = 16;
+constexpr int kMgCoarseMax = 2048;
+constexpr int kMgCoarseSweeps = 64;
+constexpr double kMgOmega = 0.8;
+
+struct Lv {
+    int nr, nz;
+    double fr, fa;        // coupling factors 2^b, 2^(2a - b)
+    const uint8_t* type;  // 0 free
+};
+
+// sum_j c (x_n - x_m) over the neighbours (held ones at zero) and the diagonal
+__device__ inline double lv_apply(const Lv& L, const double* x, int64_t n, double& diag) {
+    const int i = (int)(n % L.nr), k = (int)(n / L.nr);
+    const double cin = i > 0 ? L.fr * 2.0 * (i - 0.5) : 0.0;
+    const double cout = i < L.nr - 1 ? L.fr * 2.0 * (i + 0.5) : 0.0;
+    const double hi = fmin(i + 0.5, L.nr - 1.0), lo = fmax(i - 0.5, 0.0);
+    const double cax = L.fa * (hi * hi - lo * lo);
+    const double xn = x[n];
+    double s = 0.0;
+    if (cin != 0.0 && L.type[n - 1] == kFree) s -= cin * x[n - 1];
+    if (cout != 0.0 && L.type[n + 1] == kFree) s -= cout * x[n + 1];
+    if (k > 0 && L.type[n - L.nr] == kFree) s -= cax * x[n - L.nr];
+    if (k < L.nz - 1 && L.type[n + L.nr] == kFree) s -= cax * x[n + L.nr];
+    diag = cin + cout + 2.0 * cax;
+    return s + diag * xn;
+}
+
+// y = x + omega D^-1 (b - A x) at free nodes (zero_x: x taken as zero)
+__global__ __launch_bounds__(kBlock) void k_mg_jacobi(Lv L, const double* x, double* y, const double* b, int zero_x,
+                                                       const State* st) {
+    if (st->done) return;
+    const int64_t nn = (int64_t)L.nr * L.nz;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (int64_t)gridDim.x * blockDim.x) {
+        if (L.type[n] != kFree) continue;
+        double d;
+        if (zero_x) {
+            lv_apply(L, b, n, d);  // the diagonal only
+            y[n] = kMgOmega * b[n] / d;
+        } else {
+            const double ax = lv_apply(L, x, n, d);
+            y[n] = x[n] + kMgOmega * (b[n] - ax) / d;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_mg_resid(Lv L, const double* x, const double* b, double* t,
+                                                      const State* st) {
+    if (st->done) return;
+    const int64_t nn = (int64_t)L.nr * L.nz;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (int64_t)gridDim.x * blockDim.x) {
+        if (L.type[n] != kFree) continue;
+        double d;
+        t[n] = b[n] - lv_apply(L, x, n, d);
+    }
+}
+
+// b_c = R t (sr, sz: 2 where the dimension is halved, else 1)
+__global__ __launch_bounds__(kBlock) void k_mg_restrict(Lv F, Lv Cl, const double* t, double* bc, int sr, int sz,
+                                                         const State* st) {
+    if (st->done) return;
+    const int64_t nn = (int64_t)Cl.nr * Cl.nz;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (int64_t)gridDim.x * blockDim.x) {
+        if (Cl.type[n] != kFree) continue;
+        const int I = (int)(n % Cl.nr), K = (int)(n / Cl.nr);
+        const int i0 = sr * I, k0 = sz * K;
+        double s = 0.0;
+        for (int dk = -(sz - 1); dk <= sz - 1; ++dk) {
+            const int k = k0 + dk;
+            if (k < 0 || k >= F.nz) continue;
+            const double wk = dk == 0 ? 1.0 : 0.5;
+            for (int di = -(sr - 1); di <= sr - 1; ++di) {
+                const int i = i0 + di;
+                if (i < 0 || i >= F.nr) continue;
+                const double wi = di == 0 ? 1.0 : 0.5;
+                const int64_t m = (int64_t)k * F.nr + i;
+                if (F.type[m] == kFree) s += wi * wk * t[m];
+            }
+        }
+        bc[n] = s;
+    }
+}
+
+// x_f += P x_c at free fine nodes
+__global__ __launch_bounds__(kBlock) void k_mg_prolong(Lv F, Lv Cl, const double* xc, double* xf, int sr, int sz,
+                                                        const State* st) {
+    if (st->done) return;
+    const int64_t nn = (int64_t)F.nr * F.nz;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (int64_t)gridDim.x * blockDim.x) {
+        if (F.type[n] != kFree) continue;
+        const int i = (int)(n % F.nr), k = (int)(n / F.nr);
+        int I0 = i, I1 = i, K0 = k, K1 = k;
+        if (sr == 2) {
+            I0 = i >> 1;
+            I1 = (i + 1) >> 1;
+        }
+        if (sz == 2) {
+            K0 = k >> 1;
+            K1 = (k + 1) >> 1;
+        }
+        const double wi = I0 == I1 ? 1.0 : 0.5, wk = K0 == K1 ? 1.0 : 0.5;
+        auto at = [&](int I, int K) {
+            const int64_t m = (int64_t)K * Cl.nr + I;
+            return Cl.type[m] == kFree ? xc[m] : 0.0;
+        };
+        double v = at(I0, K0);
+        if (I1 != I0) v += at(I1, K0);
+        if (K1 != K0) {
+            v += at(I0, K1);
+            if (I1 != I0) v += at(I1, K1);
+        }
+        xf[n] += wi * wk * v;
+    }
+}
+
+// the coarsest level: kMgCoarseSweeps Jacobi sweeps from zero, in LDS, one block
+__global__ __launch_bounds__(kBlock) void k_mg_coarse(Lv L, const double* b, double* x, const State* st) {
+    if (st->done) return;
+    __shared__ double xs[2][kMgCoarseMax];
+    const int nn = L.nr * L.nz;
+    for (int n = threadIdx.x; n < nn; n += blockDim.x) xs[0][n] = 0.0;
+    __syncthreads();
+    int cur = 0;
+    for (int sweep = 0; sweep < kMgCoarseSweeps; ++sweep) {
+        for (int n = threadIdx.x; n < nn; n += blockDim.x) {
+            if (L.type[n] != kFree) {
+                xs[cur ^ 1][n] = 0.0;
+                continue;
+            }
+            double d;
+            const double ax = lv_apply(L, xs[cur], n, d);
+            xs[cur ^ 1][n] = xs[cur][n] + kMgOmega * (b[n] - ax) / d;
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    for (int n = threadIdx.x; n < nn; n += blockDim.x) x[n] = xs[cur][n];
 }
 
 __global__ void k_field(Geo g, const double* phi, double h, double* E) {
@@ -317,9 +497,10 @@ __global__ void k_zero_rho(int64_t* rho, int64_t nn) {
     if (n < nn) rho[n] = 0;
 }
 
+// tail: the slots from st->ngrp[sp] on (those added after the grouping)
 __global__ __launch_bounds__(kBlock) void k_deposit(Geo g, const double* r, const double* z, const uint32_t* id,
-                                                     const State* st, int sp, int64_t sign, int64_t* rho) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                     const State* st, int sp, int64_t sign, int64_t* rho, int tail) {
+    const int64_t p = (tail ? (int64_t)st->ngrp[sp] : 0) + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= (int64_t)st->n[sp] || id[p] == kDead) return;
     const double R = r[p], Z = z[p];
     const int i = clampi((int)floor(R), 0, g.nr - 2), k = clampi((int)floor(Z), 0, g.nz - 2);
@@ -333,11 +514,22 @@ __global__ __launch_bounds__(kBlock) void k_deposit(Geo g, const double* r, cons
     atomicAdd(q + n0 + g.nr + 1, (unsigned long long)(sign * qr * qz));
 }
 
-__global__ void k_counts(const uint32_t* id, const State* st, int sp, unsigned long long* out) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool alive = p < (int64_t)st->n[sp] && id[p] != kDead;
-    const unsigned long long m = __ballot(alive);
-    if ((threadIdx.x & 63) == 0 && m) atomicAdd(out, (unsigned long long)__popcll(m));
+// alive particles: per-thread counts over a grid-stride loop, one atomic per block
+__global__ __launch_bounds__(kBlock) void k_counts(const uint32_t* id, const State* st, int sp,
+                                                    unsigned long long* out) {
+    __shared__ unsigned long long sh[kBlock / 64];
+    const int64_t n = (int64_t)st->n[sp];
+    unsigned long long cnt = 0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
+        cnt += id[p] != kDead ? 1ull : 0ull;
+    cnt = pic::wave_sum(cnt);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int q = 0; q < kBlock / 64; ++q) t += sh[q];
+        if (t) atomicAdd(out, t);
+    }
 }
 
 __global__ void k_qsum(const int64_t* rho, int64_t nn, unsigned long long* out) {
@@ -403,9 +595,64 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(const uint32_t* in, TO* out
     if (threadIdx.x == 0) st->total = carry_s;
 }
 
-__global__ void k_zero_u32(uint32_t* x, int64_t n) {
+// The same over many blocks: k_scan_sums leaves the sum of every chunk of
+// kScanChunk counts, k_scan (one block) their exclusive prefix and the
+// total, k_scan_apply the prefix inside every chunk plus the chunk's offset.
+constexpr int kScanChunk = 4 * kScanBlock;
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums(const uint32_t* in, int64_t m, uint32_t* sums) {
+    __shared__ unsigned long long ws[kScanBlock / 64];
+    const int64_t i0 = (int64_t)blockIdx.x * kScanChunk + 4 * (int64_t)threadIdx.x;
+    unsigned long long run = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) run += i0 + k < m ? (unsigned long long)in[i0 + k] : 0ull;
+    run = pic::wave_sum(run);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = run;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t = 0;
+        for (int q = 0; q < kScanBlock / 64; ++q) t += ws[q];
+        sums[blockIdx.x] = (uint32_t)t;
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_scan_apply(const uint32_t* in, uint32_t* out, int64_t m,
+                                                            const uint32_t* offs) {
+    __shared__ unsigned long long wsum[kScanBlock / 64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i0 = (int64_t)blockIdx.x * kScanChunk + 4 * (int64_t)threadIdx.x;
+    unsigned long long v[4], run = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = i0 + k < m ? (unsigned long long)in[i0 + k] : 0ull;
+        run += v[k];
+    }
+    unsigned long long x = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned long long y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    unsigned long long pre = offs[blockIdx.x];
+    for (int q = 0; q < w; ++q) pre += wsum[q];
+    pre += x - run;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (i0 + k < m) out[i0 + k] = (uint32_t)pre;
+        pre += v[k];
+    }
+}
+
+// zero the cell counts; the slots in use are the ones being grouped
+__global__ void k_zero_u32(uint32_t* x, int64_t n, State* st) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) x[i] = 0u;
+    if (i == 0) {
+        st->nbig = 0;
+        for (int s = 0; s < 3; ++s) st->ngrp[s] = st->n[s];
+    }
 }
 
 struct CollArgs {
@@ -417,10 +664,11 @@ struct CollArgs {
     int64_t cap[3];
     State* st;
     uint32_t* cnt;     // 3 nc particles per (species, cell)
-    uint32_t* fill;    // 3 nc placement counters
+    uint32_t* cpos;    // every slot's arrival order in its cell
     uint32_t* start;   // 3 nc exclusive prefix of cnt
     uint32_t* seg;     // slots grouped by (species, cell), unordered within a cell
     uint32_t* sorted;  // the same, ascending slot (= id) order within a cell
+    uint32_t* big;     // keys of the cells above kRankSmall particles
     int32_t* cellof;   // cell of every slot (-1 free)
     uint8_t* used;     // the slot's particle had an event this step
     uint8_t* pflag;    // neutral slot: 1 impact ionization, 2 field ionization
@@ -450,7 +698,7 @@ __global__ __launch_bounds__(kBlock) void k_cells(CollArgs a, int s) {
     int32_t c = -1;
     if (a.id[s][p] != kDead) {
         c = cell_index(a.g, a.r[s][p], a.z[s][p]);
-        atomicAdd(&a.cnt[s * a.nc + c], 1u);
+        a.cpos[a.off[s] + p] = atomicAdd(&a.cnt[s * a.nc + c], 1u);
     }
     a.cellof[a.off[s] + p] = c;
     a.used[a.off[s] + p] = 0;
@@ -462,14 +710,59 @@ __global__ __launch_bounds__(kBlock) void k_place(CollArgs a, int s) {
     if (p >= (int64_t)a.st->n[s]) return;
     const int32_t c = a.cellof[a.off[s] + p];
     if (c < 0) return;
-    const int64_t key = s * a.nc + c;
-    a.seg[a.start[key] + atomicAdd(&a.fill[key], 1u)] = (uint32_t)p;
+    a.seg[a.start[s * a.nc + c] + a.cpos[a.off[s] + p]] = (uint32_t)p;
 }
 
-// Each grouped slot's rank among its cell's slots (the number of smaller
-// ones) gives its place in ascending order. The work is quadratic in the
-// particles of a cell; the lanes of a wavefront that share a cell read the
-// same addresses together.
+// The deposit of the grouped electrons and ions in grouped order: the lanes
+// of a wavefront that hold one cell add their node weights by a segmented
+// sum over the lanes, and the first of them adds the sums to the cell's four
+// nodes (integers, so the node charge does not depend on the order).
+__global__ __launch_bounds__(kBlock) void k_deposit_grouped(CollArgs a, int64_t* rho) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool act = j < (int64_t)a.start[2 * a.nc];
+    long long key = -1;
+    long long w[4] = {0, 0, 0, 0};
+    int64_t n0 = 0;
+    if (act) {
+        const int s = j < (int64_t)a.start[a.nc] ? 0 : 1;
+        const uint32_t p = a.seg[j];
+        const int32_t c = a.cellof[a.off[s] + p];
+        key = (long long)s * a.nc + c;
+        const Geo& g = a.g;
+        const double R = a.r[s][p], Z = a.z[s][p];
+        const int i = clampi((int)floor(R), 0, g.nr - 2), k = clampi((int)floor(Z), 0, g.nz - 2);
+        const int64_t qr = pic::quantize(R - i, 20), qz = pic::quantize(Z - k, 20);
+        const int64_t one = 1 << 20, sign = s == 0 ? -1 : 1;
+        n0 = (int64_t)k * g.nr + i;
+        w[0] = sign * (one - qr) * (one - qz);
+        w[1] = sign * qr * (one - qz);
+        w[2] = sign * (one - qr) * qz;
+        w[3] = sign * qr * qz;
+    }
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long kk = __shfl_down(key, o, 64);
+        const bool same = lane + o < 64 && kk == key;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const long long y = __shfl_down(w[t], o, 64);
+            if (same) w[t] += y;
+        }
+    }
+    const long long prev = __shfl_up(key, 1, 64);
+    if (!act || (lane > 0 && prev == key)) return;
+    unsigned long long* q = (unsigned long long*)rho;
+    atomicAdd(q + n0, (unsigned long long)w[0]);
+    atomicAdd(q + n0 + 1, (unsigned long long)w[1]);
+    atomicAdd(q + n0 + a.g.nr, (unsigned long long)w[2]);
+    atomicAdd(q + n0 + a.g.nr + 1, (unsigned long long)w[3]);
+}
+
+// Cells of up to kRankSmall particles of a species: each grouped slot's
+// rank among its cell's slots (the number of smaller ones) is its place in
+// ascending order; the lanes of a wavefront that share a cell read the same
+// addresses together. Larger cells are listed for k_sort_big.
 __global__ __launch_bounds__(kBlock) void k_rank(CollArgs a) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= (int64_t)a.st->total) return;  // the particles grouped, from the scan of the counts
@@ -477,9 +770,63 @@ __global__ __launch_bounds__(kBlock) void k_rank(CollArgs a) {
     const uint32_t p = a.seg[j];
     const int64_t key = s * a.nc + a.cellof[a.off[s] + p];
     const int64_t b = a.start[key], m = a.cnt[key];
+    if (m > kRankSmall) {
+        if (j == b) a.big[atomicAdd(&a.st->nbig, 1u)] = (uint32_t)key;
+        return;
+    }
     int64_t rank = 0;
     for (int64_t k = 0; k < m; ++k) rank += a.seg[b + k] < p ? 1 : 0;
     a.sorted[b + rank] = p;
+}
+
+// The listed cells, one per block in turn: up to kRankLds particles by a
+// bitonic sort in LDS (padded to a power of two with 0xFFFFFFFF, above every
+// slot), beyond that by rank counting over LDS tiles of the cell (quadratic
+// in the cell's particles).
+__global__ __launch_bounds__(kBlock) void k_sort_big(CollArgs a) {
+    __shared__ uint32_t keys[kRankLds];
+    const uint32_t nbig = a.st->nbig;
+    for (uint32_t e = blockIdx.x; e < nbig; e += gridDim.x) {
+        const int64_t key = a.big[e];
+        const int64_t b = a.start[key], m = a.cnt[key];
+        if (m <= kRankLds) {
+            int P = 1;
+            while (P < m) P <<= 1;
+            for (int i = threadIdx.x; i < P; i += blockDim.x) keys[i] = i < m ? a.seg[b + i] : 0xFFFFFFFFu;
+            __syncthreads();
+            for (int k = 2; k <= P; k <<= 1) {
+                for (int jj = k >> 1; jj > 0; jj >>= 1) {
+                    for (int i = threadIdx.x; i < P; i += blockDim.x) {
+                        const int ixj = i ^ jj;
+                        if (ixj > i) {
+                            const uint32_t x = keys[i], y = keys[ixj];
+                            if ((x > y) == ((i & k) == 0)) {
+                                keys[i] = y;
+                                keys[ixj] = x;
+                            }
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+            for (int i = threadIdx.x; i < m; i += blockDim.x) a.sorted[b + i] = keys[i];
+            __syncthreads();  // keys are reused by the next cell
+        } else {
+            for (int64_t i0 = 0; i0 < m; i0 += blockDim.x) {
+                const int64_t i = i0 + threadIdx.x;
+                const uint32_t p = i < m ? a.seg[b + i] : 0xFFFFFFFFu;
+                int64_t rank = 0;
+                for (int64_t t0 = 0; t0 < m; t0 += kRankLds) {
+                    const int64_t tn = m - t0 < kRankLds ? m - t0 : kRankLds;
+                    for (int64_t k = threadIdx.x; k < tn; k += blockDim.x) keys[k] = a.seg[b + t0 + k];
+                    __syncthreads();
+                    for (int64_t k = 0; k < tn; ++k) rank += keys[k] < p ? 1 : 0;
+                    __syncthreads();
+                }
+                if (i < m) a.sorted[b + rank] = p;
+            }
+        }
+    }
 }
 
 __device__ inline double xs_at(const CollArgs& a, int k, double E) {
@@ -810,7 +1157,45 @@ __global__ __launch_bounds__(kBlock) void k_emit_place(EmitArgs a) {
     }
 }
 
+__global__ void k_mg_types(Lv F, int cnr, int cnz, int sr, int sz, uint8_t* tc) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (int64_t)cnr * cnz) return;
+    const int I = (int)(n % cnr), K = (int)(n / cnr);
+    tc[n] = F.type[(int64_t)(sz * K) * F.nr + sr * I] == kFree ? kFree : kHeld0;
+}
+
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// the multigrid levels of a grid: dims and coupling factors
+struct MgDims {
+    int levels;
+    int nr[kMgMaxLevels], nz[kMgMaxLevels], sr[kMgMaxLevels], sz[kMgMaxLevels];  // sr, sz: halved to level l + 1
+    double fr[kMgMaxLevels], fa[kMgMaxLevels];
+};
+
+MgDims mg_dims(int nr, int nz) {
+    MgDims d{};
+    int a = 0, b = 0;
+    d.levels = 1;
+    d.nr[0] = nr;
+    d.nz[0] = nz;
+    d.fr[0] = d.fa[0] = 1.0;
+    for (int l = 0; l + 1 < kMgMaxLevels; ++l) {
+        const bool hr = (d.nr[l] - 1) % 2 == 0 && d.nr[l] - 1 >= 4;
+        const bool hz = (d.nz[l] - 1) % 2 == 0 && d.nz[l] - 1 >= 4;
+        if (!hr && !hz) break;
+        d.sr[l] = hr ? 2 : 1;
+        d.sz[l] = hz ? 2 : 1;
+        a += hr ? 1 : 0;
+        b += hz ? 1 : 0;
+        d.nr[l + 1] = hr ? (d.nr[l] - 1) / 2 + 1 : d.nr[l];
+        d.nz[l + 1] = hz ? (d.nz[l] - 1) / 2 + 1 : d.nz[l];
+        d.fr[l + 1] = std::ldexp(1.0, b);
+        d.fa[l + 1] = std::ldexp(1.0, 2 * a - b);
+        d.levels = l + 2;
+    }
+    return d;
+}
 
 int64_t patches(const pic_rz_config* c) {
     if (c->fn_rings <= 0) return 0;
@@ -823,8 +1208,11 @@ struct Work {
     State* st = nullptr;
     double *r = nullptr, *p = nullptr, *q = nullptr, *part = nullptr;  // CG
     unsigned long long* cnt = nullptr;                                   // moments counters (8)
-    uint32_t *ccnt = nullptr, *fill = nullptr, *start = nullptr;         // 3 nc each
+    uint32_t *ccnt = nullptr, *start = nullptr;                          // 3 nc each
+    uint32_t* cpos = nullptr;                                            // sum of caps
+    uint32_t *ssum = nullptr, *spre = nullptr;                           // chunk sums of the scans
     uint32_t *seg = nullptr, *sorted = nullptr;                          // sum of caps each
+    uint32_t* big = nullptr;                                             // 3 nc
     int32_t* cellof = nullptr;
     uint8_t* used = nullptr;
     uint8_t* pflag = nullptr;  // cap[2]
@@ -832,6 +1220,11 @@ struct Work {
     uint32_t *bcnt = nullptr, *bpre = nullptr;  // 2 nblk each
     uint32_t* pcnt = nullptr;                   // patches
     uint64_t* poff = nullptr;
+    double* z = nullptr;                        // preconditioned residual (nodes)
+    // multigrid levels: types (level 0: the node types), two iterates, the
+    // right-hand side (level 0: the CG residual) and the residual
+    uint8_t* mtype[kMgMaxLevels] = {};
+    double *mxa[kMgMaxLevels] = {}, *mxb[kMgMaxLevels] = {}, *mb[kMgMaxLevels] = {}, *mt[kMgMaxLevels] = {};
 };
 
 size_t layout(const pic_rz_config* c, const int64_t cap[3], char* base, Work* w) {
@@ -853,11 +1246,15 @@ size_t layout(const pic_rz_config* c, const int64_t cap[3], char* base, Work* w)
     t.q = (double*)take(nn * 8);
     t.part = (double*)take(4 * kCgBlocks * 8);
     t.cnt = (unsigned long long*)take(8 * 8);
-    t.ccnt = (uint32_t*)take(6 * nc * 4);  // counts, then the placement counters
-    t.fill = t.ccnt ? t.ccnt + 3 * nc : nullptr;
+    t.ccnt = (uint32_t*)take(3 * nc * 4);
     t.start = (uint32_t*)take(3 * nc * 4);
+    t.cpos = (uint32_t*)take(ncap * 4);
+    const size_t nscan = std::max(3 * nc, 2 * nblk) / kScanChunk + 2;
+    t.ssum = (uint32_t*)take(nscan * 4);
+    t.spre = (uint32_t*)take(nscan * 4);
     t.seg = (uint32_t*)take(ncap * 4);
     t.sorted = (uint32_t*)take(ncap * 4);
+    t.big = (uint32_t*)take(3 * nc * 4);
     t.cellof = (int32_t*)take(ncap * 4);
     t.used = (uint8_t*)take(ncap);
     t.pflag = (uint8_t*)take((size_t)cap[2]);
@@ -866,6 +1263,18 @@ size_t layout(const pic_rz_config* c, const int64_t cap[3], char* base, Work* w)
     t.bpre = (uint32_t*)take(2 * nblk * 4);
     t.pcnt = (uint32_t*)take(np * 4 + 4);
     t.poff = (uint64_t*)take(np * 8 + 8);
+    t.z = (double*)take(nn * 8);
+    const MgDims d = mg_dims(c->nr, c->nz);
+    for (int l = 0; l < d.levels; ++l) {
+        const size_t m = (size_t)d.nr[l] * d.nz[l];
+        if (l > 0) {
+            t.mtype[l] = (uint8_t*)take(m);
+            t.mb[l] = (double*)take(m * 8);
+        }
+        t.mxa[l] = (double*)take(m * 8);
+        t.mxb[l] = l == 0 ? t.z : (double*)take(m * 8);
+        t.mt[l] = (double*)take(m * 8);
+    }
     if (w) *w = t;
     return off + 256;
 }
@@ -902,12 +1311,22 @@ struct pic_rz_ctx {
     hipStream_t stream = nullptr;
     pic_rz::Geo g;
     pic_rz::Work w;
+    pic_rz::MgDims mg;
     pic_rz::State* st = nullptr;
     double *r = nullptr, *p = nullptr, *q = nullptr, *part = nullptr;
     unsigned long long* cnt = nullptr;
     double V0 = 0.0, F1 = 0.0;
     int64_t step = 0;
     int last_iters = 0;
+    // two PCG iterations of the step solve (phi = buf.phi) as one graph
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t pcg_graph = nullptr;
+    hipGraphExec_t pcg_exec = nullptr;
+    ~pic_rz_ctx() {
+        if (pcg_exec) (void)hipGraphExecDestroy(pcg_exec);
+        if (pcg_graph) (void)hipGraphDestroy(pcg_graph);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    }
     std::string err;
 };
 
@@ -936,6 +1355,7 @@ CgArgs cg_args(pic_rz_ctx* c, double* phi, double V0) {
     a.r = c->r;
     a.p = c->p;
     a.q = c->q;
+    a.z = c->w.z;
     a.part = c->part;
     a.st = c->st;
     a.qscale = std::ldexp(1.0, -40) * kQe / (kPi * kEps0 * c->cfg.h);
@@ -943,9 +1363,54 @@ CgArgs cg_args(pic_rz_ctx* c, double* phi, double V0) {
     return a;
 }
 
-// CG from the current phi (held nodes set to 0 / V0); without charge the
-// q vector, zeroed, stands for the charge (it is read only by k_cg_init,
-// before the iterations use q)
+Lv level(const pic_rz_ctx* c, int l) {
+    Lv L;
+    L.nr = c->mg.nr[l];
+    L.nz = c->mg.nz[l];
+    L.fr = c->mg.fr[l];
+    L.fa = c->mg.fa[l];
+    L.type = l == 0 ? c->buf.node_type : c->w.mtype[l];
+    return L;
+}
+
+unsigned mg_grid(const Lv& L) {
+    const int64_t nn = (int64_t)L.nr * L.nz;
+    return (unsigned)std::min<int64_t>(kCgBlocks * 4, std::max<int64_t>(1, (nn + kBlock - 1) / kBlock));
+}
+
+// x_b = M b on level l (a V-cycle below it); x_a is work space
+void vcycle(pic_rz_ctx* c, int l, const double* b, double* xa, double* xb) {
+    const Lv L = level(c, l);
+    const unsigned G = mg_grid(L);
+    const State* st = c->st;
+    if (l == c->mg.levels - 1) {
+        if ((int64_t)L.nr * L.nz <= kMgCoarseMax) {
+            hipLaunchKernelGGL(k_mg_coarse, dim3(1), dim3(kBlock), 0, c->stream, L, b, xb, st);
+        } else {
+            hipLaunchKernelGGL(k_mg_jacobi, dim3(G), dim3(kBlock), 0, c->stream, L, (const double*)xb, xa, b, 1, st);
+            hipLaunchKernelGGL(k_mg_jacobi, dim3(G), dim3(kBlock), 0, c->stream, L, (const double*)xa, xb, b, 0, st);
+            hipLaunchKernelGGL(k_mg_jacobi, dim3(G), dim3(kBlock), 0, c->stream, L, (const double*)xb, xa, b, 0, st);
+            hipLaunchKernelGGL(k_mg_jacobi, dim3(G), dim3(kBlock), 0, c->stream, L, (const double*)xa, xb, b, 0, st);
+        }
+        return;
+    }
+    const Lv Cl = level(c, l + 1);
+    const int sr = c->mg.sr[l], sz = c->mg.sz[l];
+    hipLaunchKernelGGL(k_mg_jacobi, dim3(G), dim3(kBlock), 0, c->stream, L, (const double*)xb, xa, b, 1, st);
+    hipLaunchKernelGGL(k_mg_jacobi, dim3(G), dim3(kBlock), 0, c->stream, L, (const double*)xa, xb, b, 0, st);
+    hipLaunchKernelGGL(k_mg_resid, dim3(G), dim3(kBlock), 0, c->stream, L, (const double*)xb, b, c->w.mt[l], st);
+    hipLaunchKernelGGL(k_mg_restrict, dim3(mg_grid(Cl)), dim3(kBlock), 0, c->stream, L, Cl,
+                       (const double*)c->w.mt[l], c->w.mb[l + 1], sr, sz, st);
+    vcycle(c, l + 1, c->w.mb[l + 1], c->w.mxa[l + 1], c->w.mxb[l + 1]);
+    hipLaunchKernelGGL(k_mg_prolong, dim3(G), dim3(kBlock), 0, c->stream, L, Cl, (const double*)c->w.mxb[l + 1], xb,
+                       sr, sz, st);
+    hipLaunchKernelGGL(k_mg_jacobi, dim3(G), dim3(kBlock), 0, c->stream, L, (const double*)xb, xa, b, 0, st);
+    hipLaunchKernelGGL(k_mg_jacobi, dim3(G), dim3(kBlock), 0, c->stream, L, (const double*)xa, xb, b, 0, st);
+}
+
+// Multigrid-preconditioned CG from the current phi (held nodes set to 0 /
+// V0); without charge the q vector, zeroed, stands for the charge (it is read
+// only by k_cg_init, before the iterations use q)
 pic_status cg(pic_rz_ctx* c, double* phi, double V0, bool with_charge, double rtol, int maxit, int* iters) {
     CgArgs a = cg_args(c, phi, V0);
     if (!with_charge) {
@@ -955,15 +1420,59 @@ pic_status cg(pic_rz_ctx* c, double* phi, double V0, bool with_charge, double rt
     }
     hipLaunchKernelGGL(k_cg_init, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(k_cg_start, dim3(1), dim3(64), 0, c->stream, a, rtol, maxit);
-    State h{};
-    for (;;) {
-        for (int k = 0; k < 16; ++k) {
-            hipLaunchKernelGGL(k_cg_ap, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a);
-            hipLaunchKernelGGL(k_cg_update, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a);
-            hipLaunchKernelGGL(k_cg_scalars, dim3(1), dim3(64), 0, c->stream, a);
-            hipLaunchKernelGGL(k_cg_p, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a);
+    vcycle(c, 0, c->r, c->w.mxa[0], c->w.z);
+    hipLaunchKernelGGL(k_pcg_rz, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a, 1);
+    hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(64), 0, c->stream, a, 1);
+    auto iteration = [&]() {
+        hipLaunchKernelGGL(k_cg_ap, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a);
+        hipLaunchKernelGGL(k_cg_update, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a);
+        hipLaunchKernelGGL(k_cg_check, dim3(1), dim3(64), 0, c->stream, a);
+        vcycle(c, 0, c->r, c->w.mxa[0], c->w.z);
+        hipLaunchKernelGGL(k_pcg_rz, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a, 0);
+        hipLaunchKernelGGL(k_pcg_beta, dim3(1), dim3(64), 0, c->stream, a, 0);
+        hipLaunchKernelGGL(k_cg_p, dim3(kCgBlocks), dim3(kBlock), 0, c->stream, a);
+    };
+    // The step solve replays pairs of iterations from a graph captured on a
+    // stream of its own (the kernels read the iteration state from the
+    // device and return at once after convergence, so every pair is the same
+    // launch sequence); the set-up solve launches them directly.
+    const bool use_graph = phi == c->buf.phi && with_charge;
+    if (use_graph && !c->pcg_exec) {
+        bool ok = true;
+        if (!c->cap_stream) ok = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) == hipSuccess;
+        hipStream_t keep = c->stream;
+        if (ok) ok = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        if (ok) {
+            c->stream = c->cap_stream;
+            iteration();
+            iteration();
+            c->stream = keep;
+            hipGraph_t gr = nullptr;
+            ok = hipStreamEndCapture(c->cap_stream, &gr) == hipSuccess && gr;
+            if (ok) ok = hipGraphInstantiate(&c->pcg_exec, gr, nullptr, nullptr, 0) == hipSuccess;
+            if (ok) c->pcg_graph = gr;
+            else if (gr) (void)hipGraphDestroy(gr);
         }
-        pic_status s = hip_ok(c, hipMemcpyAsync(&h, c->st, sizeof(State), hipMemcpyDeviceToHost, c->stream), "copy");
+        if (!ok) {
+            c->stream = keep;
+            (void)hipGetLastError();
+            return fail(c, PIC_E_HIP, "capture of the solver iterations failed");
+        }
+    }
+    State h{};
+    int chunk = c->last_iters > 2 ? c->last_iters : 2;
+    for (;;) {
+        if (use_graph) {
+            for (int k = 0; k < chunk; k += 2)
+                if (hipGraphLaunch(c->pcg_exec, c->stream) != hipSuccess)
+                    return fail(c, PIC_E_HIP, "graph launch failed");
+        } else {
+            for (int k = 0; k < 8; ++k) iteration();
+        }
+        chunk = 2;
+        pic_status s = hip_ok(c, hipGetLastError(), "solve");
+        if (s == PIC_OK)
+            s = hip_ok(c, hipMemcpyAsync(&h, c->st, sizeof(State), hipMemcpyDeviceToHost, c->stream), "copy");
         if (s == PIC_OK) s = hip_ok(c, hipStreamSynchronize(c->stream), "sync");
         if (s != PIC_OK) return s;
         if (h.done) break;
@@ -999,10 +1508,11 @@ CollArgs coll_args(pic_rz_ctx* c, uint32_t step) {
     }
     a.st = c->st;
     a.cnt = c->w.ccnt;
-    a.fill = c->w.fill;
+    a.cpos = c->w.cpos;
     a.start = c->w.start;
     a.seg = c->w.seg;
     a.sorted = c->w.sorted;
+    a.big = c->w.big;
     a.cellof = c->w.cellof;
     a.used = c->w.used;
     a.pflag = c->w.pflag;
@@ -1031,20 +1541,34 @@ CollArgs coll_args(pic_rz_ctx* c, uint32_t step) {
     return a;
 }
 
+// exclusive prefix of m counts into out, the total into st->total
+void scan_u32(pic_rz_ctx* c, const uint32_t* in, uint32_t* out, int64_t m) {
+    if (m <= 4 * (int64_t)kScanChunk) {
+        hipLaunchKernelGGL(k_scan<uint32_t>, dim3(1), dim3(kScanBlock), 0, c->stream, in, out, m, c->st);
+        return;
+    }
+    const int64_t nb = (m + kScanChunk - 1) / kScanChunk;
+    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(kScanBlock), 0, c->stream, in, m, c->w.ssum);
+    hipLaunchKernelGGL(k_scan<uint32_t>, dim3(1), dim3(kScanBlock), 0, c->stream, (const uint32_t*)c->w.ssum,
+                       c->w.spre, nb, c->st);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanBlock), 0, c->stream, in, out, m,
+                       (const uint32_t*)c->w.spre);
+}
+
 // (e, Cu) pairs, (Cu+, Cu) pairs, field ionization, then the products
 void collide(pic_rz_ctx* c, uint32_t step) {
     CollArgs a = coll_args(c, step);
     const int64_t ncap = c->buf.cap[0] + c->buf.cap[1] + c->buf.cap[2];
-    hipLaunchKernelGGL(k_zero_u32, dim3(grid_of(6 * a.nc)), dim3(kBlock), 0, c->stream, a.cnt, 6 * a.nc);
+    hipLaunchKernelGGL(k_zero_u32, dim3(grid_of(3 * a.nc)), dim3(kBlock), 0, c->stream, a.cnt, 3 * a.nc, c->st);
     for (int s = 0; s < 3; ++s)
         if (c->buf.cap[s] > 0)
             hipLaunchKernelGGL(k_cells, dim3(grid_of(c->buf.cap[s])), dim3(kBlock), 0, c->stream, a, s);
-    hipLaunchKernelGGL(k_scan<uint32_t>, dim3(1), dim3(kScanBlock), 0, c->stream, (const uint32_t*)a.cnt, a.start,
-                       3 * a.nc, c->st);
+    scan_u32(c, a.cnt, a.start, 3 * a.nc);
     for (int s = 0; s < 3; ++s)
         if (c->buf.cap[s] > 0)
             hipLaunchKernelGGL(k_place, dim3(grid_of(c->buf.cap[s])), dim3(kBlock), 0, c->stream, a, s);
     hipLaunchKernelGGL(k_rank, dim3(grid_of(ncap)), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(k_sort_big, dim3(kBigBlocks), dim3(kBlock), 0, c->stream, a);
     if (c->buf.cap[0] > 0)
         hipLaunchKernelGGL(k_pair, dim3(grid_of(c->buf.cap[0])), dim3(kBlock), 0, c->stream, a, 1);
     if (c->buf.cap[1] > 0)
@@ -1052,8 +1576,7 @@ void collide(pic_rz_ctx* c, uint32_t step) {
     if (c->buf.cap[2] == 0) return;
     hipLaunchKernelGGL(k_fi, dim3(grid_of(c->buf.cap[2])), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(k_prod_count, dim3((unsigned)a.nblk), dim3(kBlock), 0, c->stream, a);
-    hipLaunchKernelGGL(k_scan<uint32_t>, dim3(1), dim3(kScanBlock), 0, c->stream, (const uint32_t*)a.bcnt, a.bpre,
-                       2 * a.nblk, c->st);
+    scan_u32(c, a.bcnt, a.bpre, 2 * a.nblk);
     hipLaunchKernelGGL(k_commit, dim3(1), dim3(64), 0, c->stream, c->st, 0, c->buf.cap[0], c->buf.cap[1]);
     hipLaunchKernelGGL(k_prod_place, dim3((unsigned)a.nblk), dim3(kBlock), 0, c->stream, a);
 }
@@ -1128,6 +1651,7 @@ pic_status pic_rz_init(const pic_rz_config* cfg, const pic_rz_buffers* bufs, voi
     // 256-byte alignment of the work memory
     char* base = (char*)(((uintptr_t)bufs->scratch + 255) & ~(uintptr_t)255);
     layout(cfg, bufs->cap, base, &c->w);
+    c->mg = mg_dims(cfg->nr, cfg->nz);
     c->st = c->w.st;
     c->r = c->w.r;
     c->p = c->w.p;
@@ -1161,6 +1685,21 @@ pic_status pic_rz_init(const pic_rz_config* cfg, const pic_rz_buffers* bufs, voi
     if (s == PIC_OK) {
         hipLaunchKernelGGL(k_types, dim3(grid_of(nn)), dim3(kBlock), 0, c->stream, c->g, bufs->node_type);
         s = hip_ok(c, hipMemsetAsync(bufs->phi1, 0, nn * 8, c->stream), "zero");
+        // the multigrid levels: coarse node types, held entries of every
+        // level array at zero (they are never written)
+        for (int l = 0; l < c->mg.levels && s == PIC_OK; ++l) {
+            const int64_t m = (int64_t)c->mg.nr[l] * c->mg.nz[l];
+            if (l > 0) {
+                hipLaunchKernelGGL(k_mg_types, dim3(grid_of(m)), dim3(kBlock), 0, c->stream, level(c, l - 1),
+                                   c->mg.nr[l], c->mg.nz[l], c->mg.sr[l - 1], c->mg.sz[l - 1], c->w.mtype[l]);
+                s = hip_ok(c, hipMemsetAsync(c->w.mb[l], 0, m * 8, c->stream), "zero");
+            }
+            if (s == PIC_OK) s = hip_ok(c, hipMemsetAsync(c->w.mxa[l], 0, m * 8, c->stream), "zero");
+            if (s == PIC_OK) s = hip_ok(c, hipMemsetAsync(c->w.mxb[l], 0, m * 8, c->stream), "zero");
+            if (s == PIC_OK) s = hip_ok(c, hipMemsetAsync(c->w.mt[l], 0, m * 8, c->stream), "zero");
+        }
+        if (s == PIC_OK) s = hip_ok(c, hipMemsetAsync(c->r, 0, nn * 8, c->stream), "zero");
+        if (s == PIC_OK) s = hip_ok(c, hipMemsetAsync(c->p, 0, nn * 8, c->stream), "zero");
     }
     int it = 0;
     if (s == PIC_OK) s = cg(c, bufs->phi1, 1.0, false, cfg->laplace_rtol, 1000000, &it);
@@ -1238,11 +1777,17 @@ pic_status pic_rz_step(pic_rz_ctx* c, int32_t nsteps, uint32_t flags) {
         if (flags & PIC_RZ_DEPOSIT) {
             const int64_t nn = (int64_t)c->g.nr * c->g.nz;
             hipLaunchKernelGGL(k_zero_rho, dim3(grid_of(nn)), dim3(kBlock), 0, c->stream, c->buf.rho, nn);
+            // after this step's grouping (collisions), the grouped particles
+            // in grouped order and the ones added since; else every slot
+            const int grouped = (flags & PIC_RZ_COLLIDE) ? 1 : 0;
+            if (grouped && cap[0] + cap[1] > 0)
+                hipLaunchKernelGGL(k_deposit_grouped, dim3(grid_of(cap[0] + cap[1])), dim3(kBlock), 0, c->stream,
+                                   coll_args(c, (uint32_t)c->step), c->buf.rho);
             for (int s = 0; s < 2; ++s)
                 if (cap[s] > 0)
                     hipLaunchKernelGGL(k_deposit, dim3(grid_of(cap[s])), dim3(kBlock), 0, c->stream, c->g,
                                        c->buf.r[s], c->buf.z[s], c->buf.id[s], (const State*)c->st, s,
-                                       (int64_t)(s == 0 ? -1 : 1), c->buf.rho);
+                                       (int64_t)(s == 0 ? -1 : 1), c->buf.rho, grouped);
         }
         pic_status st = hip_ok(c, hipGetLastError(), "step");
         if (st != PIC_OK) return st;
@@ -1274,8 +1819,8 @@ pic_status pic_rz_moments(pic_rz_ctx* c, pic_rz_moments_t* out) {
     if (s != PIC_OK) return s;
     for (int sp = 0; sp < 3; ++sp)
         if (c->buf.cap[sp] > 0)
-            hipLaunchKernelGGL(k_counts, dim3(grid_of(c->buf.cap[sp])), dim3(kBlock), 0, c->stream, c->buf.id[sp],
-                               (const State*)c->st, sp, c->cnt + sp);
+            hipLaunchKernelGGL(k_counts, dim3(std::min<unsigned>(1024u, grid_of(c->buf.cap[sp]))), dim3(kBlock), 0,
+                               c->stream, c->buf.id[sp], (const State*)c->st, sp, c->cnt + sp);
     const int64_t nn = (int64_t)c->g.nr * c->g.nz;
     hipLaunchKernelGGL(k_qsum, dim3(256), dim3(kBlock), 0, c->stream, c->buf.rho, nn, c->cnt + 3);
     unsigned long long h[8];

@@ -205,3 +205,42 @@ def synthetic_potential(cfg: Config, V0: float, amp: float = 0.05, seed: int = 3
         a = amp * V0 * rng.standard_normal()
         phi = phi + a * np.sin(math.pi * kz * Z) * np.cos(math.pi * kx * X) * np.cos(math.pi * ky * Y)
     return np.ascontiguousarray(phi.reshape(-1))
+
+
+def rz_context(seed: int = 3) -> dict:
+    """The axisymmetric variant on the paper's own geometry (Sec. 2.2 and the
+    runs of Sec. 3): tip radius 50 nm, height 2.5 um (50 r), anode 7.68 um
+    above the cathode (about 150 r), radial extent 1.28 um, 5 nm spacing
+    (257 x 1537 nodes: 256 and 1536 cells, which halve down to a few nodes
+    for the multigrid preconditioner), 10 GV/m at the apex, dt = 2.5e-16 s
+    (an electron at 10^6 m/s moves 0.05 spacings a step), the synthetic
+    tables, 64 emission rings."""
+    el, iz, cx = synthetic_tables()
+    return dict(nr=257, nz=1537, h=5e-9, tip_r=50e-9, tip_h=2.5e-6, apex_field=10e9, dt=2.5e-16,
+                m_ion=CU_MASS_U * _AMU, seed=seed, xs=(1e-2, 1e4, el, iz, cx), fn_rings=64)
+
+
+def rz_load(geo: dict, counts=(4_000_000, 4_000_000, 4_000_000), r_max: float = 200.0, z_max: float = 1000.0,
+            rng: np.random.Generator | None = None) -> dict:
+    """Particles of each species uniform in volume over r < r_max, 1 < z <
+    z_max (grid units), clear of the tip by a spacing: electrons with
+    normal velocity components of 0.02 spacings a step, ions and neutrals
+    2e-4 (grid units per step). Returns species -> dict r, z, vr, vt, vz."""
+    rng = rng or np.random.default_rng(geo.get("seed", 3))
+    R, H = geo["tip_r"] / geo["h"] + 1.0, geo["tip_h"] / geo["h"] + 1.0
+    zc = H - R
+    out = {}
+    for s, n in enumerate(counts):
+        r = np.zeros(0)
+        z = np.zeros(0)
+        while len(r) < n:
+            m = int(1.2 * (n - len(r))) + 16
+            rr = r_max * np.sqrt(rng.uniform(0.0, 1.0, m))
+            zz = rng.uniform(1.0, z_max, m)
+            inside = ((zz <= zc) & (rr <= R)) | ((zz > zc) & (rr * rr + (zz - zc) ** 2 <= R * R))
+            r = np.concatenate([r, rr[~inside]])
+            z = np.concatenate([z, zz[~inside]])
+        sv = 0.02 if s == 0 else 2e-4
+        out[s] = {"r": r[:n], "z": z[:n], "vr": rng.normal(0, sv, n), "vt": rng.normal(0, sv, n),
+                  "vz": rng.normal(0, sv, n)}
+    return out

@@ -265,3 +265,58 @@ def test_rz_capacity_and_ids():
               "vz": np.zeros(2)}}
     with pytest.raises(rz.PicError):
         rz.RZSimulation(**GEOM, load=ld, ids={2: np.array([5, 4], np.uint32)})
+
+
+def test_rz_collide_dense_cells():
+    """Cells beyond the per-thread ranks (more than 64 particles of a species:
+    the LDS sort) and beyond the LDS sort (more than 4096: rank counting),
+    over a background load."""
+    print("case: rz collide dense cells", flush=True)
+    o0 = RZ(GEOM["nr"], GEOM["nz"], GEOM["h"], GEOM["tip_r"], GEOM["tip_h"], GEOM["apex_field"], GEOM["dt"],
+            GEOM["m_ion"])
+    rng = np.random.default_rng(12)
+    base = _load(o0, rng, (2000, 800, 2000))
+    dense = {0: [((5, 40), 150), ((10, 45), 300)], 1: [((5, 40), 200), ((12, 50), 90)],
+             2: [((5, 40), 5000), ((10, 45), 100), ((12, 50), 700)]}
+    load = {}
+    for s in range(3):
+        parts = [base[s]]
+        for (i, k), m in dense[s]:
+            sv = (0.05, 0.002, 0.001)[s]
+            parts.append({"r": i + rng.uniform(0.01, 0.99, m), "z": k + rng.uniform(0.01, 0.99, m),
+                          "vr": rng.normal(0, sv, m), "vt": rng.normal(0, sv, m), "vz": rng.normal(0, sv, m)})
+        load[s] = {key: np.concatenate([p[key] for p in parts]) for key in ("r", "z", "vr", "vt", "vz")}
+    g, o = _pair_all(seed=17, load=load)
+    for step in range(3):
+        g.step(1, rz.PIC_RZ_COLLIDE | rz.PIC_RZ_ADVANCE)
+        o.collide()
+        o.step_no += 1
+        _compare_all(g, o, 1e-12)
+    m = g.moments()
+    assert np.array_equal(m["events"], o.events), (m["events"], o.events)
+    assert o.events[1] > 100 and o.events[3] > 50, o.events
+
+
+def test_rz_multigrid_levels_solve():
+    """A grid whose cell counts halve (32 x 80 cells: five multigrid levels):
+    the unit-anode potential and a solve with charge as the oracle's direct
+    solution, in a few preconditioned iterations."""
+    print("case: rz multigrid levels", flush=True)
+    geom = dict(GEOM, nr=33, nz=81)
+    o = RZ(geom["nr"], geom["nz"], geom["h"], geom["tip_r"], geom["tip_h"], geom["apex_field"], geom["dt"],
+           geom["m_ion"])
+    load = _load(o, np.random.default_rng(41), (20000, 8000, 0))
+    nid = 0
+    for s in range(3):
+        m = len(load[s]["r"])
+        o.load(s, load[s], np.arange(nid, nid + m))
+        nid += m
+    g = rz.RZSimulation(**geom, load=load, laplace_rtol=1e-13, step_rtol=1e-12)
+    assert np.abs(g.grid("phi1") - o.phi1).max() <= 1e-10
+    g.step(1, rz.PIC_RZ_DEPOSIT)
+    o.deposit()
+    info = g.solve(1e-12, 1000)
+    o.solve()
+    assert info["converged"] and info["iterations"] <= 20, info
+    phi = g.grid("phi")
+    assert np.abs(phi - o.phi).max() <= 1e-9 * np.abs(o.phi).max()
