@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <string>
+#include <vector>
 
 #include "pic_internal.hpp"
 #include "pic_rz.h"
@@ -311,12 +312,14 @@ __device__ inline double lv_apply(const Lv& L, const double* x, int64_t n, doubl
     return s + diag * xn;
 }
 
+// The level operations over nodes n0, n0 + stride, ... (a grid-stride loop
+// in the kernels of one level, a block-stride loop in k_mg_small).
+
 // y = x + omega D^-1 (b - A x) at free nodes (zero_x: x taken as zero)
-__global__ __launch_bounds__(kBlock) void k_mg_jacobi(Lv L, const double* x, double* y, const double* b, int zero_x,
-                                                       const State* st) {
-    if (st->done) return;
+__device__ inline void mg_jacobi(const Lv& L, const double* x, double* y, const double* b, int zero_x, int64_t n0,
+                                 int64_t stride) {
     const int64_t nn = (int64_t)L.nr * L.nz;
-    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t n = n0; n < nn; n += stride) {
         if (L.type[n] != kFree) continue;
         double d;
         if (zero_x) {
@@ -329,23 +332,33 @@ __global__ __launch_bounds__(kBlock) void k_mg_jacobi(Lv L, const double* x, dou
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_mg_resid(Lv L, const double* x, const double* b, double* t,
-                                                      const State* st) {
-    if (st->done) return;
+__device__ inline void mg_resid(const Lv& L, const double* x, const double* b, double* t, int64_t n0,
+                                int64_t stride) {
     const int64_t nn = (int64_t)L.nr * L.nz;
-    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t n = n0; n < nn; n += stride) {
         if (L.type[n] != kFree) continue;
         double d;
         t[n] = b[n] - lv_apply(L, x, n, d);
     }
 }
 
-// b_c = R t (sr, sz: 2 where the dimension is halved, else 1)
-__global__ __launch_bounds__(kBlock) void k_mg_restrict(Lv F, Lv Cl, const double* t, double* bc, int sr, int sz,
-                                                         const State* st) {
+__global__ __launch_bounds__(kBlock) void k_mg_jacobi(Lv L, const double* x, double* y, const double* b, int zero_x,
+                                                       const State* st) {
     if (st->done) return;
+    mg_jacobi(L, x, y, b, zero_x, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_mg_resid(Lv L, const double* x, const double* b, double* t,
+                                                      const State* st) {
+    if (st->done) return;
+    mg_resid(L, x, b, t, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
+}
+
+// b_c = R t (sr, sz: 2 where the dimension is halved, else 1)
+__device__ inline void mg_restrict(const Lv& F, const Lv& Cl, const double* t, double* bc, int sr, int sz,
+                                   int64_t n0, int64_t stride) {
     const int64_t nn = (int64_t)Cl.nr * Cl.nz;
-    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t n = n0; n < nn; n += stride) {
         if (Cl.type[n] != kFree) continue;
         const int I = (int)(n % Cl.nr), K = (int)(n / Cl.nr);
         const int i0 = sr * I, k0 = sz * K;
@@ -366,12 +379,18 @@ __global__ __launch_bounds__(kBlock) void k_mg_restrict(Lv F, Lv Cl, const doubl
     }
 }
 
-// x_f += P x_c at free fine nodes
-__global__ __launch_bounds__(kBlock) void k_mg_prolong(Lv F, Lv Cl, const double* xc, double* xf, int sr, int sz,
-                                                        const State* st) {
+__global__ __launch_bounds__(kBlock) void k_mg_restrict(Lv F, Lv Cl, const double* t, double* bc, int sr, int sz,
+                                                         const State* st) {
     if (st->done) return;
+    mg_restrict(F, Cl, t, bc, sr, sz, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+                (int64_t)gridDim.x * blockDim.x);
+}
+
+// x_f += P x_c at free fine nodes
+__device__ inline void mg_prolong(const Lv& F, const Lv& Cl, const double* xc, double* xf, int sr, int sz,
+                                  int64_t n0, int64_t stride) {
     const int64_t nn = (int64_t)F.nr * F.nz;
-    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t n = n0; n < nn; n += stride) {
         if (F.type[n] != kFree) continue;
         const int i = (int)(n % F.nr), k = (int)(n / F.nr);
         int I0 = i, I1 = i, K0 = k, K1 = k;
@@ -398,10 +417,15 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong(Lv F, Lv Cl, const double
     }
 }
 
-// the coarsest level: kMgCoarseSweeps Jacobi sweeps from zero, in LDS, one block
-__global__ __launch_bounds__(kBlock) void k_mg_coarse(Lv L, const double* b, double* x, const State* st) {
+__global__ __launch_bounds__(kBlock) void k_mg_prolong(Lv F, Lv Cl, const double* xc, double* xf, int sr, int sz,
+                                                        const State* st) {
     if (st->done) return;
-    __shared__ double xs[2][kMgCoarseMax];
+    mg_prolong(F, Cl, xc, xf, sr, sz, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
+               (int64_t)gridDim.x * blockDim.x);
+}
+
+// the coarsest level: kMgCoarseSweeps Jacobi sweeps from zero, in LDS, one block
+__device__ inline void mg_coarse(const Lv& L, const double* b, double* x, double (*xs)[kMgCoarseMax]) {
     const int nn = L.nr * L.nz;
     for (int n = threadIdx.x; n < nn; n += blockDim.x) xs[0][n] = 0.0;
     __syncthreads();
@@ -420,6 +444,64 @@ __global__ __launch_bounds__(kBlock) void k_mg_coarse(Lv L, const double* b, dou
         cur ^= 1;
     }
     for (int n = threadIdx.x; n < nn; n += blockDim.x) x[n] = xs[cur][n];
+}
+
+__global__ __launch_bounds__(kBlock) void k_mg_coarse(Lv L, const double* b, double* x, const State* st) {
+    if (st->done) return;
+    __shared__ double xs[2][kMgCoarseMax];
+    mg_coarse(L, b, x, xs);
+}
+
+// The levels from l0 down, when level l0 has at most kMgSmallNodes nodes:
+// the whole V-cycle below the caller in one block of kMgSmallBlock threads,
+// the phases separated by barriers (the arrays are the block's own).
+constexpr int kMgSmallNodes = 2048;
+constexpr int kMgSmallBlock = 1024;
+
+struct MgSmall {
+    int l0, levels;
+    Lv lv[kMgMaxLevels];
+    const double* b[kMgMaxLevels];
+    double *xa[kMgMaxLevels], *xb[kMgMaxLevels], *t[kMgMaxLevels], *bw[kMgMaxLevels];
+    int sr[kMgMaxLevels], sz[kMgMaxLevels];
+};
+
+__global__ __launch_bounds__(kMgSmallBlock) void k_mg_small(MgSmall m, const State* st) {
+    if (st->done) return;
+    __shared__ double xs[2][kMgCoarseMax];
+    const int64_t t0 = threadIdx.x, T = blockDim.x;
+    const int last = m.levels - 1;
+    for (int l = m.l0; l < last; ++l) {
+        mg_jacobi(m.lv[l], m.xb[l], m.xa[l], m.b[l], 1, t0, T);
+        __syncthreads();
+        mg_jacobi(m.lv[l], m.xa[l], m.xb[l], m.b[l], 0, t0, T);
+        __syncthreads();
+        mg_resid(m.lv[l], m.xb[l], m.b[l], m.t[l], t0, T);
+        __syncthreads();
+        mg_restrict(m.lv[l], m.lv[l + 1], m.t[l], m.bw[l + 1], m.sr[l], m.sz[l], t0, T);
+        __syncthreads();
+    }
+    const Lv& C = m.lv[last];
+    if ((int64_t)C.nr * C.nz <= kMgCoarseMax) {
+        mg_coarse(C, m.b[last], m.xb[last], xs);
+    } else {
+        mg_jacobi(C, m.xb[last], m.xa[last], m.b[last], 1, t0, T);
+        __syncthreads();
+        mg_jacobi(C, m.xa[last], m.xb[last], m.b[last], 0, t0, T);
+        __syncthreads();
+        mg_jacobi(C, m.xb[last], m.xa[last], m.b[last], 0, t0, T);
+        __syncthreads();
+        mg_jacobi(C, m.xa[last], m.xb[last], m.b[last], 0, t0, T);
+    }
+    __syncthreads();
+    for (int l = last - 1; l >= m.l0; --l) {
+        mg_prolong(m.lv[l], m.lv[l + 1], m.xb[l + 1], m.xb[l], m.sr[l], m.sz[l], t0, T);
+        __syncthreads();
+        mg_jacobi(m.lv[l], m.xb[l], m.xa[l], m.b[l], 0, t0, T);
+        __syncthreads();
+        mg_jacobi(m.lv[l], m.xa[l], m.xb[l], m.b[l], 0, t0, T);
+        __syncthreads();
+    }
 }
 
 __global__ void k_field(Geo g, const double* phi, double h, double* E) {
@@ -665,6 +747,7 @@ struct CollArgs {
     State* st;
     uint32_t* cnt;     // 3 nc particles per (species, cell)
     uint32_t* cpos;    // every slot's arrival order in its cell
+    uint32_t* crank;   // every slot's rank (id order) in its cell
     uint32_t* start;   // 3 nc exclusive prefix of cnt
     uint32_t* seg;     // slots grouped by (species, cell), unordered within a cell
     uint32_t* sorted;  // the same, ascending slot (= id) order within a cell
@@ -680,6 +763,7 @@ struct CollArgs {
     const double* xs;
     int xs_n;
     double xs_emin, xs_lnr;
+    double sig_max[2];  // per class: the largest table value of sigma_el + sigma_iz, of sigma_cx (a bound)
     double h, dt, m_ion, xi;
     uint64_t seed;
     uint32_t step;
@@ -777,6 +861,7 @@ __global__ __launch_bounds__(kBlock) void k_rank(CollArgs a) {
     int64_t rank = 0;
     for (int64_t k = 0; k < m; ++k) rank += a.seg[b + k] < p ? 1 : 0;
     a.sorted[b + rank] = p;
+    a.crank[a.off[s] + p] = (uint32_t)rank;
 }
 
 // The listed cells, one per block in turn: up to kRankLds particles by a
@@ -809,7 +894,11 @@ __global__ __launch_bounds__(kBlock) void k_sort_big(CollArgs a) {
                     __syncthreads();
                 }
             }
-            for (int i = threadIdx.x; i < m; i += blockDim.x) a.sorted[b + i] = keys[i];
+            const int sp = (int)(key / a.nc);
+            for (int i = threadIdx.x; i < m; i += blockDim.x) {
+                a.sorted[b + i] = keys[i];
+                a.crank[a.off[sp] + keys[i]] = (uint32_t)i;
+            }
             __syncthreads();  // keys are reused by the next cell
         } else {
             for (int64_t i0 = 0; i0 < m; i0 += blockDim.x) {
@@ -823,7 +912,10 @@ __global__ __launch_bounds__(kBlock) void k_sort_big(CollArgs a) {
                     for (int64_t k = 0; k < tn; ++k) rank += keys[k] < p ? 1 : 0;
                     __syncthreads();
                 }
-                if (i < m) a.sorted[b + rank] = p;
+                if (i < m) {
+                    a.sorted[b + rank] = p;
+                    a.crank[a.off[key / a.nc] + p] = (uint32_t)rank;
+                }
             }
         }
     }
@@ -853,13 +945,15 @@ __device__ inline void iso(double ct, double ph, double out[3]) {
 // at most one thread of the class.
 __global__ __launch_bounds__(kBlock) void k_pair(CollArgs a, int cls) {
     const int sa = cls == 1 ? 0 : 1;
-    const int64_t j = (int64_t)a.start[sa * a.nc] + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= (int64_t)a.start[(sa + 1) * a.nc]) return;
-    const uint32_t pa0 = a.sorted[j];
+    // one thread per grouped slot of the charged species, in slot order (its
+    // own reads and writes coalesce), with its rank in the cell
+    const int64_t pa0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (pa0 >= (int64_t)a.st->ngrp[sa]) return;
     const int32_t c = a.cellof[a.off[sa] + pa0];
+    if (c < 0) return;
     const int64_t NA = a.cnt[sa * a.nc + c], NB = a.cnt[2 * a.nc + c];
     if (NB == 0) return;
-    const int64_t qa = j - (int64_t)a.start[sa * a.nc + c];
+    const int64_t qa = a.crank[a.off[sa] + pa0];
     const int64_t bB = a.start[2 * a.nc + c];
     const bool a_proj = NA <= NB;
     const int64_t NT = a_proj ? NB : NA;
@@ -874,7 +968,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(CollArgs a, int cls) {
         if (q >= NB) return;
         pb = a.sorted[bB + q];
     }
-    const uint32_t pa = pa0;
+    const uint32_t pa = (uint32_t)pa0;
     if (cls == 2 && a.used[a.off[2] + pb]) return;
     const uint32_t pid = a_proj ? a.id[sa][pa] : a.id[2][pb];
     const double h = a.h, dt = a.dt;
@@ -885,6 +979,13 @@ __global__ __launch_bounds__(kBlock) void k_pair(CollArgs a, int cls) {
     const double u[3] = {(vA[0] - vB[0]) * h / dt, (vA[1] - vB[1]) * h / dt, (vA[2] - vB[2]) * h / dt};
     const double um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
     const double ma = cls == 1 ? kMe : a.m_ion, mb = a.m_ion;
+    const int i = c % (a.g.nr - 1);
+    const double vol = kPi * (double)(2 * i + 1) * h * h * h;
+    const double n = (double)NT / vol;
+    const Draw2 d = draw2(a.seed, pid, a.step, cls == 1 ? pic::kTagMcc1 : pic::kTagMcc2, 0);
+    // the largest cross section of the class bounds P from above: a draw at
+    // or above that bound is no collision, without the table look-ups
+    if (!(d.a < -expm1(-um * n * a.sig_max[cls - 1] * dt))) return;
     const double E = 0.5 * ma * um * um / kQe;
     double sig0, sig1 = 0.0;
     if (cls == 1) {
@@ -894,11 +995,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(CollArgs a, int cls) {
         sig0 = xs_at(a, 2, E);
     }
     const double stot = sig0 + sig1;
-    const int i = c % (a.g.nr - 1);
-    const double vol = kPi * (double)(2 * i + 1) * h * h * h;
-    const double n = (double)NT / vol;
     const double P = -expm1(-um * n * stot * dt);
-    const Draw2 d = draw2(a.seed, pid, a.step, cls == 1 ? pic::kTagMcc1 : pic::kTagMcc2, 0);
     if (!(d.a < P)) return;
     int proc = cls == 1 ? 1 : 0;
     if (cls == 1 && d.b * stot < sig0) proc = 0;
@@ -1209,7 +1306,7 @@ struct Work {
     double *r = nullptr, *p = nullptr, *q = nullptr, *part = nullptr;  // CG
     unsigned long long* cnt = nullptr;                                   // moments counters (8)
     uint32_t *ccnt = nullptr, *start = nullptr;                          // 3 nc each
-    uint32_t* cpos = nullptr;                                            // sum of caps
+    uint32_t *cpos = nullptr, *crank = nullptr;                          // sum of caps each
     uint32_t *ssum = nullptr, *spre = nullptr;                           // chunk sums of the scans
     uint32_t *seg = nullptr, *sorted = nullptr;                          // sum of caps each
     uint32_t* big = nullptr;                                             // 3 nc
@@ -1249,6 +1346,7 @@ size_t layout(const pic_rz_config* c, const int64_t cap[3], char* base, Work* w)
     t.ccnt = (uint32_t*)take(3 * nc * 4);
     t.start = (uint32_t*)take(3 * nc * 4);
     t.cpos = (uint32_t*)take(ncap * 4);
+    t.crank = (uint32_t*)take(ncap * 4);
     const size_t nscan = std::max(3 * nc, 2 * nblk) / kScanChunk + 2;
     t.ssum = (uint32_t*)take(nscan * 4);
     t.spre = (uint32_t*)take(nscan * 4);
@@ -1318,6 +1416,7 @@ struct pic_rz_ctx {
     double V0 = 0.0, F1 = 0.0;
     int64_t step = 0;
     int last_iters = 0;
+    double sig_max[2] = {0.0, 0.0};  // bounds of the class cross sections, from the tables
     // two PCG iterations of the step solve (phi = buf.phi) as one graph
     hipStream_t cap_stream = nullptr;
     hipGraph_t pcg_graph = nullptr;
@@ -1383,6 +1482,23 @@ void vcycle(pic_rz_ctx* c, int l, const double* b, double* xa, double* xb) {
     const Lv L = level(c, l);
     const unsigned G = mg_grid(L);
     const State* st = c->st;
+    if ((int64_t)L.nr * L.nz <= kMgSmallNodes && l < c->mg.levels - 1) {
+        MgSmall m{};
+        m.l0 = l;
+        m.levels = c->mg.levels;
+        for (int k = l; k < c->mg.levels; ++k) {
+            m.lv[k] = level(c, k);
+            m.b[k] = k == l ? b : c->w.mb[k];
+            m.bw[k] = k == l ? nullptr : c->w.mb[k];
+            m.xa[k] = k == l ? xa : c->w.mxa[k];
+            m.xb[k] = k == l ? xb : c->w.mxb[k];
+            m.t[k] = c->w.mt[k];
+            m.sr[k] = c->mg.sr[k];
+            m.sz[k] = c->mg.sz[k];
+        }
+        hipLaunchKernelGGL(k_mg_small, dim3(1), dim3(kMgSmallBlock), 0, c->stream, m, st);
+        return;
+    }
     if (l == c->mg.levels - 1) {
         if ((int64_t)L.nr * L.nz <= kMgCoarseMax) {
             hipLaunchKernelGGL(k_mg_coarse, dim3(1), dim3(kBlock), 0, c->stream, L, b, xb, st);
@@ -1509,6 +1625,7 @@ CollArgs coll_args(pic_rz_ctx* c, uint32_t step) {
     a.st = c->st;
     a.cnt = c->w.ccnt;
     a.cpos = c->w.cpos;
+    a.crank = c->w.crank;
     a.start = c->w.start;
     a.seg = c->w.seg;
     a.sorted = c->w.sorted;
@@ -1525,6 +1642,8 @@ CollArgs coll_args(pic_rz_ctx* c, uint32_t step) {
     a.xs_n = c->cfg.xs_n;
     a.xs_emin = c->cfg.xs_emin;
     a.xs_lnr = std::log(c->cfg.xs_emax / c->cfg.xs_emin);
+    a.sig_max[0] = c->sig_max[0];
+    a.sig_max[1] = c->sig_max[1];
     a.h = c->cfg.h;
     a.dt = c->cfg.dt;
     a.m_ion = c->cfg.m_ion;
@@ -1652,6 +1771,20 @@ pic_status pic_rz_init(const pic_rz_config* cfg, const pic_rz_buffers* bufs, voi
     char* base = (char*)(((uintptr_t)bufs->scratch + 255) & ~(uintptr_t)255);
     layout(cfg, bufs->cap, base, &c->w);
     c->mg = mg_dims(cfg->nr, cfg->nz);
+    if (cfg->xs_n > 0) {
+        // an interpolated value exceeds the largest node at most by rounding
+        std::vector<double> t((size_t)3 * cfg->xs_n);
+        if (hipMemcpy(t.data(), bufs->xs, t.size() * 8, hipMemcpyDeviceToHost) != hipSuccess) {
+            delete c;
+            return PIC_E_HIP;
+        }
+        for (int k = 0; k < cfg->xs_n; ++k) {
+            c->sig_max[0] = std::max(c->sig_max[0], t[k] + t[cfg->xs_n + k]);
+            c->sig_max[1] = std::max(c->sig_max[1], t[2 * cfg->xs_n + k]);
+        }
+        c->sig_max[0] *= 1.0 + 1e-12;
+        c->sig_max[1] *= 1.0 + 1e-12;
+    }
     c->st = c->w.st;
     c->r = c->w.r;
     c->p = c->w.p;
