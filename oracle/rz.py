@@ -46,7 +46,9 @@ import scipy.sparse.linalg as spla
 FREE, DIR0, DIRV = 0, 1, 2
 ALIVE, CATHODE, ANODE, SIDE, TIP = 0, 1, 2, 3, 4
 TAG_MCC1, TAG_MCC2, TAG_PAIR1, TAG_PAIR2, TAG_FI, TAG_INJ = 1, 2, 3, 4, 5, 6
+TAG_PAIR3, TAG_MCC3 = 36, 37
 XI_CU = 7.726380            # first ionization energy of Cu [eV]
+XI2_CU = 20.29239           # second ionization energy of Cu [eV]
 
 
 class RZ:
@@ -67,14 +69,17 @@ class RZ:
     with zero velocity."""
 
     def __init__(self, nr, nz, h, tip_r, tip_h, apex_field, dt, m_ion, seed=1, xs=None, xi=XI_CU,
-                 phi_w=4.5, fn_rings=16):
+                 phi_w=4.5, fn_rings=16, cu2=False, xi2=XI2_CU):
         self.nr, self.nz, self.h, self.dt, self.m_ion = nr, nz, h, dt, m_ion
         self.seed, self.xi, self.phi_w, self.fn_rings = seed, xi, phi_w, fn_rings
-        # cross-section tables (emin, emax, el, iz, cx) on log-spaced energies
+        # cross-section tables (emin, emax, el, iz, cx[, iz2, izi]) on
+        # log-spaced energies; with cu2 also Cu + e -> Cu2+ + 3e (iz2) and
+        # Cu+ + e -> Cu2+ + 2e (izi), the ions carrying a charge state q
         self.xs = xs
+        self.cu2, self.xi2 = cu2, xi2
         self.next_id = 0
         self.step_no = 0
-        self.events = np.zeros(5, np.int64)
+        self.events = np.zeros(7, np.int64)
         self.injected = 0
         self.last_events = []
         self.R, self.H = tip_r / h, tip_h / h
@@ -181,8 +186,12 @@ class RZ:
 
     # -- particles -------------------------------------------------------------
     def load(self, s, arrays, ids):
-        self.sp[s] = {k: np.asarray(v, np.float64).copy() for k, v in arrays.items()}
+        self.sp[s] = {k: np.asarray(arrays[k], np.float64).copy() for k in ("r", "z", "vr", "vt", "vz")}
         self.sp[s]["id"] = np.asarray(ids, np.uint32).copy()
+        if s == 1:
+            q = arrays.get("q")
+            self.sp[s]["q"] = (np.asarray(q, np.uint8).copy() if q is not None
+                               else np.ones(len(ids), np.uint8))
         if len(ids):
             self.next_id = max(self.next_id, int(np.max(ids)) + 1)
 
@@ -193,14 +202,15 @@ class RZ:
             self._cfg = oracle._Config(phi_w=self.phi_w, xi=self.xi, h=self.h, dt=self.dt, seed=self.seed)
             if self.xs is not None:
                 emin, emax = self.xs[0], self.xs[1]
-                self._tabs = [np.ascontiguousarray(t, np.float64) for t in self.xs[2:5]]
+                self._tabs = [np.ascontiguousarray(t, np.float64) for t in self.xs[2:]]
                 self._cfg.xs_n, self._cfg.xs_emin, self._cfg.xs_emax = len(self._tabs[0]), emin, emax
             self._L = oracle.lib()
         return self._L, self._cfg
 
     def xs_at(self, k, E):
-        """Cross section k (0 elastic, 1 ionization, 2 charge exchange) at E
-        [eV]: the 3D oracle's table interpolation."""
+        """Cross section k (0 elastic, 1 ionization, 2 charge exchange, 3
+        double ionization of Cu, 4 ionization of Cu+) at E [eV]: the 3D
+        oracle's table interpolation."""
         L, c = self._c()
         return L.orc_xs(C.byref(c), self._tabs[k], E)
 
@@ -263,9 +273,14 @@ class RZ:
         if self.sp[s] is None:
             self.sp[s] = {k: np.zeros(0) for k in ("r", "z", "vr", "vt", "vz")}
             self.sp[s]["id"] = np.zeros(0, np.uint32)
+            if s == 1:
+                self.sp[s]["q"] = np.zeros(0, np.uint8)
         for k in ("r", "z", "vr", "vt", "vz"):
             self.sp[s][k] = np.concatenate([self.sp[s][k], np.asarray(new[k], np.float64)])
         self.sp[s]["id"] = np.concatenate([self.sp[s]["id"], np.asarray(new["id"], np.uint32)])
+        if s == 1:
+            q = new.get("q", [1] * len(new["id"]))
+            self.sp[s]["q"] = np.concatenate([self.sp[s]["q"], np.asarray(q, np.uint8)])
 
     # -- collisions -------------------------------------------------------------------
     @staticmethod
@@ -291,12 +306,16 @@ class RZ:
         return k * (self.nr - 1) + i
 
     def collide(self):
-        """(e, Cu) pairs (elastic, impact ionization), then (Cu+, Cu) pairs
-        (charge exchange), field ionization of the neutrals without an
-        event, then the products (impact before field ionization, ascending
-        neutral id; ion id first, then the electron's). Returns the events
-        as (kind, id_a, id_b), kind 1 elastic, 2 ionization, 3 charge
-        exchange, 4 field ionization."""
+        """(e, Cu) pairs (elastic, impact ionization; with cu2 also double
+        ionization), (Cu+, Cu) pairs (charge exchange), with cu2 (e, Cu+)
+        pairs (ionization of Cu+ to Cu2+), then field ionization of the
+        neutrals without an event, then the products: impact ionizations,
+        then field ionizations, each in ascending neutral id, then the
+        ionized ions in ascending ion id; a product's ion (if new) takes the
+        next id, its new electrons the following ones. Returns the events as
+        (kind, id_a, id_b): 1 elastic, 2 impact ionization, 3 charge
+        exchange, 4 field ionization, 5 double ionization of Cu, 6
+        ionization of Cu+."""
         h, dt = self.h, self.dt
         V = ("vr", "vt", "vz")
         for s in range(3):
@@ -304,25 +323,28 @@ class RZ:
                 self._append(s, {k: [] for k in ("r", "z", "vr", "vt", "vz", "id")})
         cells = [self.cell_of(s) for s in range(3)]
         used = [np.zeros(len(self.sp[s]["id"]), bool) for s in range(3)]
-        prods = []            # (kind, neutral id, neutral index, new electron velocity)
+        prods = []            # (kind, key id, index, charge state of the new ion, new electron velocities)
         events = []
         N = self.sp[2]
-        for cls in (1, 2):
-            sa = 0 if cls == 1 else 1
-            A = self.sp[sa]
-            ma, mb = (sc.m_e if cls == 1 else self.m_ion), self.m_ion
+        I = self.sp[1]
+        for cls in ((1, 2, 3) if self.cu2 else (1, 2)):
+            sa = 1 if cls == 2 else 0
+            sb = 1 if cls == 3 else 2
+            A, B = self.sp[sa], self.sp[sb]
+            ma, mb = (self.m_ion if cls == 2 else sc.m_e), self.m_ion
             mu = ma * mb / (ma + mb)
+            tag_pair, tag = {1: (TAG_PAIR1, TAG_MCC1), 2: (TAG_PAIR2, TAG_MCC2), 3: (TAG_PAIR3, TAG_MCC3)}[cls]
             for c in np.unique(cells[sa]):
                 ia = np.flatnonzero(cells[sa] == c)
-                ib = np.flatnonzero(cells[2] == c)
+                ib = np.flatnonzero(cells[sb] == c)
                 if len(ib) == 0:
                     continue
                 ia = ia[np.argsort(A["id"][ia])]
-                ib = ib[np.argsort(N["id"][ib])]
+                ib = ib[np.argsort(B["id"][ib])]
                 a_proj = len(ia) <= len(ib)
                 P_, T_ = (ia, ib) if a_proj else (ib, ia)
                 NT = len(T_)
-                uc, _ = self.draw2(int(c), self.step_no, TAG_PAIR1 if cls == 1 else TAG_PAIR2, 0)
+                uc, _ = self.draw2(int(c), self.step_no, tag_pair, 0)
                 shift = min(int(math.floor(uc * NT)), NT - 1)
                 vol = math.pi * (2 * int(c % (self.nr - 1)) + 1) * h * h * h
                 n = NT / vol
@@ -331,17 +353,23 @@ class RZ:
                     xa, xb = (pp, tt) if a_proj else (tt, pp)
                     if cls == 2 and used[2][xb]:
                         continue
-                    pid = int((A if a_proj else N)["id"][pp])
-                    u = [(A[k][xa] - N[k][xb]) * h / dt for k in V]
+                    if cls == 3 and (used[0][xa] or used[1][xb] or B["q"][xb] != 1):
+                        continue
+                    pid = int((A if a_proj else B)["id"][pp])
+                    u = [(A[k][xa] - B[k][xb]) * h / dt for k in V]
                     um = math.sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2])
                     E = 0.5 * ma * um * um / sc.e
                     if cls == 1:
                         sig = [self.xs_at(0, E), self.xs_at(1, E) if E > self.xi else 0.0]
-                    else:
+                        if self.cu2:
+                            sig.append(self.xs_at(3, E) if E > self.xi + self.xi2 else 0.0)
+                    elif cls == 2:
                         sig = [self.xs_at(2, E)]
+                    else:
+                        sig = [self.xs_at(4, E) if E > self.xi2 else 0.0]
                     stot = sum(sig)
                     P = -math.expm1(-um * n * stot * dt)
-                    U1, U2 = self.draw2(pid, self.step_no, TAG_MCC1 if cls == 1 else TAG_MCC2, 0)
+                    U1, U2 = self.draw2(pid, self.step_no, tag, 0)
                     if not U1 < P:
                         continue
                     proc, cum = len(sig) - 1, 0.0
@@ -351,12 +379,12 @@ class RZ:
                             proc = kk
                             break
                     used[sa][xa] = True
-                    used[2][xb] = True
+                    used[sb][xb] = True
                     if cls == 2:
                         for k in V:
                             A[k][xa], N[k][xb] = N[k][xb], A[k][xa]
                         events.append((3, int(A["id"][xa]), int(N["id"][xb])))
-                    elif proc == 0:
+                    elif cls == 1 and proc == 0:
                         u3, u4 = self.draw2(pid, self.step_no, TAG_MCC1, 1)
                         du = self._du(u, 2.0 * u3 - 1.0, 2.0 * math.pi * u4)
                         ka, kb = mu / ma * dt / h, mu / mb * dt / h
@@ -364,7 +392,7 @@ class RZ:
                             A[k][xa] = A[k][xa] + ka * d
                             N[k][xb] = N[k][xb] - kb * d
                         events.append((1, int(A["id"][xa]), int(N["id"][xb])))
-                    else:
+                    elif cls == 1 and proc == 1:
                         c1, p1 = self.draw2(pid, self.step_no, TAG_MCC1, 1)
                         c2, p2 = self.draw2(pid, self.step_no, TAG_MCC1, 2)
                         u5, _ = self.draw2(pid, self.step_no, TAG_MCC1, 3)
@@ -378,8 +406,49 @@ class RZ:
                         vn = [N[k][xb] * h / dt for k in V]
                         for j, k in enumerate(V):
                             A[k][xa] = (vn[j] + w1 * s1[j]) * dt / h
-                        prods.append((0, int(N["id"][xb]), xb, [(vn[j] + w2 * s2[j]) * dt / h for j in range(3)]))
+                        prods.append((0, int(N["id"][xb]), xb, 1, [[(vn[j] + w2 * s2[j]) * dt / h for j in range(3)]]))
                         events.append((2, int(A["id"][xa]), int(N["id"][xb])))
+                    elif cls == 1:
+                        # Cu + e -> Cu2+ + 3e: in the neutral's frame the
+                        # energy above xi + xi2 is shared as U5, U6 (1 - U5),
+                        # the rest by the three electrons, each isotropic
+                        c1, p1 = self.draw2(pid, self.step_no, TAG_MCC1, 1)
+                        c2, p2 = self.draw2(pid, self.step_no, TAG_MCC1, 2)
+                        u5, u6 = self.draw2(pid, self.step_no, TAG_MCC1, 3)
+                        c3, p3 = self.draw2(pid, self.step_no, TAG_MCC1, 4)
+                        dirs = [self._iso(2.0 * cc - 1.0, 2.0 * math.pi * pp_) for cc, pp_ in
+                                ((c1, p1), (c2, p2), (c3, p3))]
+                        rest = E - self.xi - self.xi2
+                        f1 = u5 * rest
+                        f2 = u6 * (rest - f1)
+                        f3 = rest - f1 - f2
+                        ws = [math.sqrt(2.0 * f * sc.e / sc.m_e) for f in (f1, f2, f3)]
+                        vn = [N[k][xb] * h / dt for k in V]
+                        for j, k in enumerate(V):
+                            A[k][xa] = (vn[j] + ws[0] * dirs[0][j]) * dt / h
+                        new_e = [[(vn[j] + ws[m] * dirs[m][j]) * dt / h for j in range(3)] for m in (1, 2)]
+                        prods.append((0, int(N["id"][xb]), xb, 2, new_e))
+                        events.append((5, int(A["id"][xa]), int(N["id"][xb])))
+                    else:
+                        # Cu+ + e -> Cu2+ + 2e: as the impact ionization of a
+                        # neutral, in the ion's frame, above xi2; the ion keeps
+                        # its place, id and velocity and takes charge state 2
+                        c1, p1 = self.draw2(pid, self.step_no, TAG_MCC3, 1)
+                        c2, p2 = self.draw2(pid, self.step_no, TAG_MCC3, 2)
+                        u5, _ = self.draw2(pid, self.step_no, TAG_MCC3, 3)
+                        s1 = self._iso(2.0 * c1 - 1.0, 2.0 * math.pi * p1)
+                        s2 = self._iso(2.0 * c2 - 1.0, 2.0 * math.pi * p2)
+                        rest3 = E - self.xi2
+                        g1 = u5 * rest3
+                        g2 = rest3 - g1
+                        v1 = math.sqrt(2.0 * g1 * sc.e / sc.m_e)
+                        v2 = math.sqrt(2.0 * g2 * sc.e / sc.m_e)
+                        vi = [I[k][xb] * h / dt for k in V]
+                        for j, k in enumerate(V):
+                            A[k][xa] = (vi[j] + v1 * s1[j]) * dt / h
+                        I["q"][xb] = 2
+                        prods.append((2, int(I["id"][xb]), xb, 0, [[(vi[j] + v2 * s2[j]) * dt / h for j in range(3)]]))
+                        events.append((6, int(A["id"][xa]), int(I["id"][xb])))
         # field ionization (Eq. dfi), none above the barrier-suppression field
         ebsi = 1.5 * self.xi ** 1.5
         for p in range(len(N["id"])):
@@ -393,21 +462,30 @@ class RZ:
             U, _ = self.draw2(int(N["id"][p]), self.step_no, TAG_FI, 0)
             if pdt > U:
                 used[2][p] = True
-                prods.append((1, int(N["id"][p]), p, [N[k][p] for k in V]))
+                prods.append((1, int(N["id"][p]), p, 1, [[N[k][p] for k in V]]))
                 events.append((4, 0xFFFFFFFF, int(N["id"][p])))
         prods.sort(key=lambda t: (t[0], t[1]))
-        ions = {k: [] for k in ("r", "z", "vr", "vt", "vz", "id")}
+        ions = {k: [] for k in ("r", "z", "vr", "vt", "vz", "id", "q")}
         els = {k: [] for k in ("r", "z", "vr", "vt", "vz", "id")}
         gone = np.zeros(len(N["id"]), bool)
-        for kind, nid, xb, ve in prods:
-            for dst, v, idv in ((ions, [N[k][xb] for k in V], self.next_id), (els, ve, self.next_id + 1)):
-                dst["r"].append(N["r"][xb])
-                dst["z"].append(N["z"][xb])
-                for k, x in zip(V, v):
-                    dst[k].append(x)
-                dst["id"].append(idv)
-            self.next_id += 2
-            gone[xb] = True
+        for kind, key, x, qnew, ves in prods:
+            src = I if kind == 2 else N
+            if kind != 2:
+                ions["r"].append(N["r"][x])
+                ions["z"].append(N["z"][x])
+                for k in V:
+                    ions[k].append(N[k][x])
+                ions["id"].append(self.next_id)
+                ions["q"].append(qnew)
+                self.next_id += 1
+                gone[x] = True
+            for ve in ves:
+                els["r"].append(src["r"][x])
+                els["z"].append(src["z"][x])
+                for k, v in zip(V, ve):
+                    els[k].append(v)
+                els["id"].append(self.next_id)
+                self.next_id += 1
         self._append(1, ions)
         self._append(0, els)
         for k in N:
@@ -424,11 +502,13 @@ class RZ:
             d = self.sp[s]
             if d is None or len(d["r"]) == 0:
                 continue
-            kq = self.charges[s] / self.masses[s] * self.dt ** 2 / self.h
+            kq0 = self.charges[s] / self.masses[s] * self.dt ** 2 / self.h
             keep = np.ones(len(d["r"]), bool)
             for p in range(len(d["r"])):
                 r, z = d["r"][p], d["z"][p]
                 vr, vt, vz = d["vr"][p], d["vt"][p], d["vz"][p]
+                # a Cu2+ ion (charge state 2) feels twice the force of Cu+
+                kq = kq0 * float(d["q"][p]) if s == 1 else kq0
                 if kq != 0.0:
                     er, ez = self.gather(r, z)
                     vr += kq * er
@@ -463,11 +543,12 @@ class RZ:
     def deposit(self):
         """Node charge in units of 2^-40 e (exact integers)."""
         Q = np.zeros(self.nr * self.nz, np.int64)
-        for s, sign in ((0, -1), (1, 1)):
+        for s, sign0 in ((0, -1), (1, 1)):
             d = self.sp[s]
             if d is None:
                 continue
-            for r, z in zip(d["r"], d["z"]):
+            for p, (r, z) in enumerate(zip(d["r"], d["z"])):
+                sign = sign0 * (int(d["q"][p]) if s == 1 else 1)
                 i, k, fr, fz = self._cell(r, z)
                 qr, qz = self._q(fr, 20), self._q(fz, 20)
                 n = k * self.nr + i

@@ -158,9 +158,8 @@ RZ_MUTATIONS = [
      "A[k][xa], N[k][xb] = N[k][xb], A[k][xa]", "A[k][xa] = N[k][xb]", RZC.pin_cx_swap),
     ("ionization energy without the threshold", "collide", "erem = E - self.xi", "erem = E",
      RZC.pin_ionization),
-    ("ion and electron ids swapped", "collide",
-     "(ions, [N[k][xb] for k in V], self.next_id), (els, ve, self.next_id + 1)",
-     "(ions, [N[k][xb] for k in V], self.next_id + 1), (els, ve, self.next_id)", RZC.pin_ionization),
+    ("ion id one too high", "collide",
+     'ions["id"].append(self.next_id)', 'ions["id"].append(self.next_id + 1)', RZC.pin_ionization),
     ("field-ionization probability with dt in seconds", "collide",
      "pdt = self.adk_rate(Eg) * (dt * 1e15)", "pdt = self.adk_rate(Eg) * dt", RZC.pin_field_ionization),
     ("field ionization above the barrier-suppression field", "collide",
@@ -173,6 +172,18 @@ RZ_MUTATIONS = [
      RZC.pin_emission_geometry),
     ("electrons started on the surface", "emit", "new[\"r\"].append(r + 1e-3 * nr_)", "new[\"r\"].append(r)",
      RZC.pin_emission_geometry),
+    ("double ionization without the second threshold", "collide", "rest = E - self.xi - self.xi2",
+     "rest = E - self.xi", RZC.pin_double_ionization),
+    ("Cu2+ ionized again", "collide", " or B[\"q\"][xb] != 1", "", RZC.pin_ion_ionization),
+    ("Cu+ ionization above xi instead of xi2", "collide", "rest3 = E - self.xi2", "rest3 = E - self.xi",
+     RZC.pin_ion_ionization),
+    ("Cu+ ionization density over the full cell volume h^3", "collide",
+     "vol = math.pi * (2 * int(c % (self.nr - 1)) + 1) * h * h * h", "vol = h * h * h",
+     RZC.pin_ion_ionization_rate),
+    ("Cu2+ kick as for Cu+", "push", "kq = kq0 * float(d[\"q\"][p]) if s == 1 else kq0", "kq = kq0",
+     RZC.pin_cu2_push_deposit),
+    ("Cu2+ deposit as for Cu+", "deposit", "sign = sign0 * (int(d[\"q\"][p]) if s == 1 else 1)",
+     "sign = sign0", RZC.pin_cu2_push_deposit),
 ]
 
 

@@ -27,19 +27,23 @@ import numpy as np
 import pytest
 import scipy.constants as sc
 
-from oracle.rz import RZ, XI_CU
+from oracle.rz import RZ, XI2_CU, XI_CU
 
 M_CU = 63.546 * sc.atomic_mass
 EMIN, EMAX, NTAB = 1e-2, 1e4, 64
 
 
-def _tables(el=0.0, iz=0.0, cx=0.0):
+def _tables(el=0.0, iz=0.0, cx=0.0, iz2=None, izi=None):
     E = EMIN * (EMAX / EMIN) ** (np.arange(NTAB) / (NTAB - 1))
-    return (EMIN, EMAX, np.full(NTAB, el), np.where(E > XI_CU, iz, 0.0), np.full(NTAB, cx))
+    t = (EMIN, EMAX, np.full(NTAB, el), np.where(E > XI_CU, iz, 0.0), np.full(NTAB, cx))
+    if iz2 is not None:
+        t = t + (np.where(E > XI_CU + XI2_CU, iz2, 0.0), np.where(E > XI2_CU, izi, 0.0))
+    return t
 
 
 def _rz(xs=None, apex=10e9, seed=7, nr=24, nz=48):
-    return RZ(nr, nz, 2e-9, 4e-9, 40e-9, apex, 5e-17, M_CU, seed=seed, xs=xs)
+    cu2 = xs is not None and len(xs) > 5
+    return RZ(nr, nz, 2e-9, 4e-9, 40e-9, apex, 5e-17, M_CU, seed=seed, xs=xs, cu2=cu2)
 
 
 def _fill(o, rng, counts, cells, speed, rest_neutrals=False):
@@ -71,12 +75,15 @@ def _vel(d, p):
     return np.array([d["vr"][p], d["vt"][p], d["vz"][p]])
 
 
+_SP_A = {1: 0, 2: 0, 3: 1, 5: 0, 6: 0}
+_SP_B = {1: 2, 2: 2, 3: 2, 4: 2, 5: 2, 6: 1}
+
+
 def _participation(ev):
     seen = set()
     for kind, a, b in ev:
-        for x in ((0 if kind in (1, 2) else 1, a), (2, b)):
-            if kind == 4 and x[0] != 2:
-                continue
+        xs = ((_SP_B[kind], b),) if kind == 4 else ((_SP_A[kind], a), (_SP_B[kind], b))
+        for x in xs:
             assert x not in seen, ("twice", kind, x)
             seen.add(x)
 
@@ -251,6 +258,150 @@ def pin_emission_count():
     want = want_step * steps
     assert want > 50, want
     assert abs(got - want) <= 5.0 * math.sqrt(want) + 1.0, (got, want)
+
+
+def pin_double_ionization():
+    """Cu + e -> Cu2+ + 3e: the ion at the neutral's place and velocity with
+    charge state 2, three electrons sharing E - xi - xi2 in the neutral's
+    frame, the ids in neutral-id order (ion, then two electrons)."""
+    o = _rz(_tables(iz2=1e-16, izi=0.0))
+    rng = np.random.default_rng(13)
+    _fill(o, rng, (9, 0, 11), [(i, k) for i in (4, 12) for k in (27, 31, 35)], (0.12, 0.0, 0.002))
+    before = copy.deepcopy(o.sp)
+    nid0 = o.next_id
+    ev = o.collide()
+    assert len(ev) > 10 and all(k == 5 for k, _, _ in ev), ev[:3]
+    _participation(ev)
+    sv = o.h / o.dt
+    ia, ib = _by_id(before[0]), _by_id(before[2])
+    je, jion = _by_id(o.sp[0]), _by_id(o.sp[1])
+    order = sorted(b for _, _, b in ev)
+    for _, a, b in ev:
+        r = order.index(b)
+        ion, e1, e2 = nid0 + 3 * r, nid0 + 3 * r + 1, nid0 + 3 * r + 2
+        assert ion in jion and e1 in je and e2 in je and e1 not in jion, (ion, e1, e2)
+        pn = ib[b]
+        vn = _vel(before[2], pn)
+        assert o.sp[1]["q"][jion[ion]] == 2
+        assert np.array_equal(_vel(o.sp[1], jion[ion]), vn)
+        for j in (jion[ion],):
+            assert o.sp[1]["r"][j] == before[2]["r"][pn] and o.sp[1]["z"][j] == before[2]["z"][pn]
+        for e in (e1, e2):
+            assert o.sp[0]["r"][je[e]] == before[2]["r"][pn] and o.sp[0]["z"][je[e]] == before[2]["z"][pn]
+        u = (_vel(before[0], ia[a]) - vn) * sv
+        E = 0.5 * sc.m_e * (u @ u) / sc.e
+        w = [(_vel(o.sp[0], je[x]) - vn) * sv for x in (a, e1, e2)]
+        E3 = 0.5 * sc.m_e * sum(x @ x for x in w) / sc.e
+        assert E3 == pytest.approx(E - XI_CU - XI2_CU, rel=1e-9, abs=1e-9)
+    assert o.next_id == nid0 + 3 * len(ev)
+
+
+def pin_ion_ionization():
+    """Cu+ + e -> Cu2+ + 2e: the ion keeps its place, id and velocity and
+    takes charge state 2; the two electrons share E - xi2 in the ion's
+    frame; ions already at charge state 2 are not ionized again."""
+    o = _rz(_tables(iz2=0.0, izi=1e-16))
+    rng = np.random.default_rng(14)
+    cells = [(i, k) for i in (4, 12) for k in (27, 31, 35)]
+    _fill(o, rng, (9, 11, 0), cells, (0.1, 0.002, 0.0))
+    o.sp[1]["q"][::3] = 2
+    before = copy.deepcopy(o.sp)
+    nid0 = o.next_id
+    ev = o.collide()
+    assert len(ev) > 10 and all(k == 6 for k, _, _ in ev), ev[:3]
+    _participation(ev)
+    sv = o.h / o.dt
+    ia, ii = _by_id(before[0]), _by_id(before[1])
+    je, jion = _by_id(o.sp[0]), _by_id(o.sp[1])
+    order = sorted(b for _, _, b in ev)
+    for _, a, b in ev:
+        assert before[1]["q"][ii[b]] == 1
+        assert o.sp[1]["q"][jion[b]] == 2
+        assert np.array_equal(_vel(o.sp[1], jion[b]), _vel(before[1], ii[b]))
+        e = nid0 + order.index(b)
+        assert e in je
+        assert o.sp[0]["r"][je[e]] == before[1]["r"][ii[b]] and o.sp[0]["z"][je[e]] == before[1]["z"][ii[b]]
+        vi = _vel(before[1], ii[b])
+        u = (_vel(before[0], ia[a]) - vi) * sv
+        E = 0.5 * sc.m_e * (u @ u) / sc.e
+        w = [(_vel(o.sp[0], je[x]) - vi) * sv for x in (a, e)]
+        E2 = 0.5 * sc.m_e * sum(x @ x for x in w) / sc.e
+        assert E2 == pytest.approx(E - XI2_CU, rel=1e-9, abs=1e-9)
+    assert o.next_id == nid0 + len(ev)
+    assert int((o.sp[1]["q"] == 2).sum()) == int((before[1]["q"] == 2).sum()) + len(ev)
+
+
+def pin_ion_ionization_rate():
+    """Electrons of one speed against Cu+ at rest in cells of columns 0-5:
+    the count over 30 steps against the sum of the pair probabilities with
+    the annular cell volume."""
+    sig = 1e-17
+    o = _rz(_tables(iz2=0.0, izi=sig), seed=19)
+    rng = np.random.default_rng(15)
+    cells = [(i, k) for i in range(6) for k in (26, 30, 34, 38)]
+    nE, nI = 6, 10
+    speed = 0.1
+    _fill(o, rng, (nE, nI, 0), cells, (speed, 0.0, 0.0))
+    u = speed * o.h / o.dt
+    want = 0.0
+    for (i, k) in cells:
+        vol = math.pi * (2 * i + 1) * o.h ** 3
+        want += nE * (1.0 - math.exp(-u * (nI / vol) * sig * o.dt))
+    want *= 30
+    state = copy.deepcopy(o.sp)
+    nid = o.next_id
+    got = 0
+    for step in range(30):
+        o.sp = copy.deepcopy(state)
+        o.next_id = nid
+        o.step_no = step
+        got += sum(1 for k, _, _ in o.collide() if k == 6)
+    assert abs(got - want) <= 5.0 * math.sqrt(want), (got, want)
+    assert want > 100, want
+
+
+def pin_cu2_push_deposit():
+    """A Cu2+ ion takes twice the kick of a Cu+ ion at the same place and
+    deposits twice its charge."""
+    o = _rz(_tables(iz2=0.0, izi=0.0), apex=12e9)
+    r = np.array([6.3, 6.3, 9.1, 9.1])
+    z = np.array([30.2, 30.2, 33.7, 33.7])
+    zero = np.zeros(4)
+    o.load(1, {"r": r, "z": z, "vr": zero, "vt": zero, "vz": zero, "q": [1, 2, 1, 2]}, np.arange(4))
+    o.push()
+    d = o.sp[1]
+    for a, b in ((0, 1), (2, 3)):
+        assert d["vz"][b] == 2.0 * d["vz"][a] and d["vr"][b] == 2.0 * d["vr"][a]
+        assert d["vz"][a] != 0.0
+    Q = o.deposit()
+    assert int(Q.sum()) == (1 + 2 + 1 + 2) * 2 ** 40
+
+
+def test_double_ionization():
+    pin_double_ionization()
+
+
+def test_ion_ionization():
+    pin_ion_ionization()
+
+
+def test_ion_ionization_rate():
+    pin_ion_ionization_rate()
+
+
+def test_cu2_push_deposit():
+    pin_cu2_push_deposit()
+
+
+def test_all_processes_one_event_each():
+    """Every process at once: no particle in two events of a step."""
+    o = _rz(_tables(el=3e-17, iz=3e-17, cx=5e-16, iz2=3e-17, izi=5e-17), apex=14e9)
+    rng = np.random.default_rng(16)
+    _fill(o, rng, (12, 10, 14), [(i, k) for i in (3, 7, 11) for k in range(24, 30)], (0.12, 0.003, 0.001))
+    ev = o.collide()
+    kinds = {k for k, _, _ in ev}
+    assert {1, 2, 3, 5, 6} <= kinds, kinds
+    _participation(ev)
 
 
 def test_elastic_conservation():
