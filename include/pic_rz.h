@@ -8,8 +8,9 @@
  * finite-volume form solved by FP64 conjugate gradients, the node field,
  * the gather, push, rotation and removal of electrons, Cu+ ions and Cu
  * neutrals, the fixed-point charge deposit, the pair collisions of Table
- * colls (elastic e-Cu, impact ionization, charge exchange Cu+-Cu; Eqs. colp,
- * du, newv), field ionization of Cu (Eq. dfi) and Fowler-Nordheim emission
+ * colls (elastic e-Cu, impact ionization, charge exchange Cu+-Cu, and with
+ * cu2 the double ionization of Cu and the ionization of Cu+; Eqs. colp, du,
+ * newv), field ionization of Cu (Eq. dfi) and Fowler-Nordheim emission
  * (Sec. 2.3.1). Superparticle weights, same-species and Coulomb collisions,
  * recombination, evaporation and the circuit of the 3D library are not part
  * of this variant.
@@ -46,9 +47,18 @@
  * neutrals that had an event; then field ionization of the remaining
  * neutrals below the barrier-suppression field 1.5 xi^1.5 GV/m; then the
  * products, impact ionizations before field ionizations, each in ascending
- * neutral id: the r-th product takes ion id next_id + 2 r and electron id
- * next_id + 2 r + 1, appended at slot n[1] + r and n[0] + r; the ionized
- * neutral's slot is freed. Emission (PIC_RZ_EMIT): fn_rings equal-area
+ * neutral id; each product's new ion (if any) takes the next id and the
+ * next ion slot, its new electrons the following ids and the next electron
+ * slots; the ionized neutral's slot is freed. With cu2 the ions carry a
+ * charge state (1 or 2; kick and deposit scale with it): the (e, Cu) class
+ * has a third process, Cu + e -> Cu2+ + 3e above xi + xi2 (the energy above
+ * it shared by the three electrons as U5, U6 (1 - U5) and the rest, draws
+ * 1 to 4 of the pair), and a third class pairs electrons with ions after
+ * the (Cu+, Cu) class: Cu+ + e -> Cu2+ + 2e above xi2 (draw tags 36 for the
+ * cell shift, 37 for the pair), the ion keeping its slot, id and velocity;
+ * particles with an event this step and Cu2+ ions sit out; these products
+ * come after the field ionizations, in ascending ion id, one new electron
+ * each. Emission (PIC_RZ_EMIT): fn_rings equal-area
  * rings of the cap, then rings one spacing high on the cylinder, each with
  * the Murphy-Good current J at the field phi(s + n) / h one spacing out
  * along the normal from its mid point s; N = J A h^2 dt / e electrons, floor(N)
@@ -89,6 +99,11 @@ typedef struct pic_rz_config {
     double xs_emin, xs_emax; /* energy range of the cross-section tables [eV], log-spaced */
     int32_t xs_n;          /* table length, >= 2 (0: no tables; PIC_RZ_COLLIDE then fails) */
     int32_t fn_rings;      /* rings on the cap (0: no emission; PIC_RZ_EMIT then fails) */
+    /* Cu2+ (Table colls: Cu + e -> Cu2+ + 3e, Cu+ + e -> Cu2+ + 2e) as the
+     * charge state of an ion; 0: every ion is Cu+ */
+    int32_t cu2;
+    int32_t reserved3;
+    double xi2;            /* second ionization energy of Cu [eV] */
 } pic_rz_config;
 
 typedef struct pic_rz_buffers {
@@ -109,8 +124,12 @@ typedef struct pic_rz_buffers {
     uint8_t* node_type;    /* nr*nz: 0 free, 1 held at 0 V, 2 held at V0 */
     void* scratch;         /* pic_rz_scratch_size bytes, 256-byte aligned */
     size_t scratch_bytes;
-    const double* xs;      /* 3 * xs_n cross sections [m^2]: elastic, ionization,
-                              charge exchange at xs_emin (xs_emax / xs_emin)^(k / (xs_n - 1)) */
+    const double* xs;      /* 3 * xs_n cross sections [m^2] (5 * xs_n with cu2): elastic,
+                              ionization, charge exchange (, double ionization of Cu,
+                              ionization of Cu+) at xs_emin (xs_emax / xs_emin)^(k / (xs_n - 1)),
+                              all >= 0 */
+    uint8_t* charge;       /* with cu2: cap[1] charge states of the ions (1 or 2; the first
+                              n[1] given at pic_rz_init), kept by the library */
 } pic_rz_buffers;
 
 typedef struct pic_rz_moments_t {
@@ -126,6 +145,9 @@ typedef struct pic_rz_moments_t {
     int64_t events[5];       /* cumulative: 1 elastic, 2 impact ionization, 3 charge exchange, 4 field ionization */
     int64_t injected;        /* cumulative emitted electrons */
     int64_t next_id;         /* id of the next new particle */
+    int64_t double_ionizations; /* cumulative Cu + e -> Cu2+ + 3e */
+    int64_t ion_ionizations;    /* cumulative Cu+ + e -> Cu2+ + 2e */
+    int64_t n_cu2;              /* alive ions of charge state 2 */
 } pic_rz_moments_t;
 
 typedef struct pic_rz_ctx pic_rz_ctx;

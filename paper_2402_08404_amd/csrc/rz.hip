@@ -29,6 +29,7 @@ using pic::kQe;
 constexpr int kCgBlocks = 256;  // blocks of the CG kernels (one partial each, summed in block order)
 constexpr uint8_t kFree = 0, kHeld0 = 1, kHeldV = 2;  // node types
 
+constexpr uint32_t kTagPairIon = 36, kTagIon = 37;  // the (e, Cu+) class: cell shift, pair draws
 constexpr int kScanBlock = 1024;  // threads of the single-block scans
 constexpr int kRankSmall = 64;    // cells up to this many particles of a species: one rank per thread
 constexpr int kRankLds = 4096;    // up to this many: one block sorts the cell in LDS
@@ -40,7 +41,8 @@ struct State {
     int it, maxit, done, error;
     unsigned long long n[3];       // slots in use per species
     unsigned long long next_id;    // id of the next new particle
-    unsigned long long events[5];  // 1 elastic, 2 impact ionization, 3 charge exchange, 4 field ionization
+    unsigned long long events[7];  // 1 elastic, 2 impact ionization, 3 charge exchange, 4 field ionization,
+                                   // 5 double ionization of Cu, 6 ionization of Cu+
     unsigned long long injected;
     unsigned long long base_n[2], base_id;  // first electron / ion slot and first id of the stage's new particles
     unsigned long long total;      // total of the last scan
@@ -521,6 +523,7 @@ struct PushArgs {
     Geo g;
     double *r, *z, *vr, *vt, *vz;
     uint32_t* id;
+    const uint8_t* charge;  // ions with Cu2+: charge states (the kick scales with them)
     const double* E;
     double kq;  // (q / m) dt^2 / h
     int sp;
@@ -532,7 +535,8 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs a) {
     if (p >= (int64_t)a.st->n[a.sp] || a.id[p] == kDead) return;
     const Geo& g = a.g;
     double r = a.r[p], z = a.z[p], vr = a.vr[p], vt = a.vt[p], vz = a.vz[p];
-    if (a.kq != 0.0) {
+    const double kq = a.charge ? a.kq * (double)a.charge[p] : a.kq;
+    if (kq != 0.0) {
         const int i = clampi((int)floor(r), 0, g.nr - 2), k = clampi((int)floor(z), 0, g.nz - 2);
         const double fr = r - i, fz = z - k;
         const int64_t n0 = (int64_t)k * g.nr + i;
@@ -541,8 +545,8 @@ __global__ __launch_bounds__(kBlock) void k_push(PushArgs a) {
                           w11 * a.E[2 * (n0 + g.nr + 1)];
         const double ez = w00 * a.E[2 * n0 + 1] + w10 * a.E[2 * (n0 + 1) + 1] + w01 * a.E[2 * (n0 + g.nr) + 1] +
                           w11 * a.E[2 * (n0 + g.nr + 1) + 1];
-        vr += a.kq * er;
-        vz += a.kq * ez;
+        vr += kq * er;
+        vz += kq * ez;
     }
     const double x = r + vr, y = vt;
     z += vz;
@@ -581,9 +585,11 @@ __global__ void k_zero_rho(int64_t* rho, int64_t nn) {
 
 // tail: the slots from st->ngrp[sp] on (those added after the grouping)
 __global__ __launch_bounds__(kBlock) void k_deposit(Geo g, const double* r, const double* z, const uint32_t* id,
-                                                     const State* st, int sp, int64_t sign, int64_t* rho, int tail) {
+                                                     const State* st, int sp, int64_t sign0, int64_t* rho, int tail,
+                                                     const uint8_t* charge) {
     const int64_t p = (tail ? (int64_t)st->ngrp[sp] : 0) + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= (int64_t)st->n[sp] || id[p] == kDead) return;
+    const int64_t sign = charge ? sign0 * (int64_t)charge[p] : sign0;
     const double R = r[p], Z = z[p];
     const int i = clampi((int)floor(R), 0, g.nr - 2), k = clampi((int)floor(Z), 0, g.nz - 2);
     const int64_t qr = pic::quantize(R - i, 20), qz = pic::quantize(Z - k, 20);
@@ -596,14 +602,15 @@ __global__ __launch_bounds__(kBlock) void k_deposit(Geo g, const double* r, cons
     atomicAdd(q + n0 + g.nr + 1, (unsigned long long)(sign * qr * qz));
 }
 
-// alive particles: per-thread counts over a grid-stride loop, one atomic per block
+// alive particles (with q, those of charge state 2): per-thread counts over
+// a grid-stride loop, one atomic per block
 __global__ __launch_bounds__(kBlock) void k_counts(const uint32_t* id, const State* st, int sp,
-                                                    unsigned long long* out) {
+                                                    unsigned long long* out, const uint8_t* q = nullptr) {
     __shared__ unsigned long long sh[kBlock / 64];
     const int64_t n = (int64_t)st->n[sp];
     unsigned long long cnt = 0;
     for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x)
-        cnt += id[p] != kDead ? 1ull : 0ull;
+        cnt += (id[p] != kDead && (!q || q[p] == 2)) ? 1ull : 0ull;
     cnt = pic::wave_sum(cnt);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = cnt;
     __syncthreads();
@@ -631,6 +638,12 @@ __global__ void k_check_ids(const uint32_t* id, int64_t n, State* st) {
     const uint32_t v = id[p];
     if (v == kDead || (p + 1 < n && v >= id[p + 1])) atomicOr(&st->skip, 1);
     if (p + 1 == n) atomicMax(&st->next_id, (unsigned long long)v + 1ull);
+}
+
+// Initial ion charge states: 1 or 2.
+__global__ void k_check_charge(const uint8_t* q, int64_t n, State* st) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n && q[p] != 1 && q[p] != 2) atomicOr(&st->skip, 1);
 }
 
 // Exclusive prefix sums of m counts in one block of kScanBlock threads, in
@@ -754,16 +767,21 @@ struct CollArgs {
     uint32_t* big;     // keys of the cells above kRankSmall particles
     int32_t* cellof;   // cell of every slot (-1 free)
     uint8_t* used;     // the slot's particle had an event this step
-    uint8_t* pflag;    // neutral slot: 1 impact ionization, 2 field ionization
-    double* ve;        // neutral slot: new electron's velocity of an impact ionization
-    uint32_t* bcnt;    // per block of neutral slots: impact, then field-ionization counts
-    uint32_t* bpre;    // their exclusive prefix
-    int64_t nblk;      // blocks of neutral slots
+    uint8_t* pflag;    // neutral slot: 1 impact ionization, 2 field ionization, 3 double ionization
+    double* ve;        // neutral slot: the new electrons' velocities of an impact ionization (2 x 3)
+    uint8_t* iflag;    // ion slot: 1 ionized to Cu2+ this step
+    double* vei;       // ion slot: the new electron's velocity of that ionization
+    uint8_t* charge;   // ion charge states (Cu2+ only)
+    uint32_t *pci, *pce;  // per product entry (impact, field, ion ionization): new ions, new electrons
+    uint32_t *ppi, *ppe;  // their exclusive prefixes
     const double* E;
     const double* xs;
     int xs_n;
     double xs_emin, xs_lnr;
-    double sig_max[2];  // per class: the largest table value of sigma_el + sigma_iz, of sigma_cx (a bound)
+    double sig_max[3];  // per class: the largest tabulated sigma_el + sigma_iz (+ sigma_iz2), sigma_cx,
+                        // sigma_izi (bounds)
+    int cu2;
+    double xi2;
     double h, dt, m_ion, xi;
     uint64_t seed;
     uint32_t step;
@@ -787,6 +805,7 @@ __global__ __launch_bounds__(kBlock) void k_cells(CollArgs a, int s) {
     a.cellof[a.off[s] + p] = c;
     a.used[a.off[s] + p] = 0;
     if (s == 2) a.pflag[p] = 0;
+    if (s == 1) a.iflag[p] = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_place(CollArgs a, int s) {
@@ -816,7 +835,7 @@ __global__ __launch_bounds__(kBlock) void k_deposit_grouped(CollArgs a, int64_t*
         const double R = a.r[s][p], Z = a.z[s][p];
         const int i = clampi((int)floor(R), 0, g.nr - 2), k = clampi((int)floor(Z), 0, g.nz - 2);
         const int64_t qr = pic::quantize(R - i, 20), qz = pic::quantize(Z - k, 20);
-        const int64_t one = 1 << 20, sign = s == 0 ? -1 : 1;
+        const int64_t one = 1 << 20, sign = s == 0 ? -1 : (a.charge ? (int64_t)a.charge[p] : 1);
         n0 = (int64_t)k * g.nr + i;
         w[0] = sign * (one - qr) * (one - qz);
         w[1] = sign * qr * (one - qz);
@@ -940,24 +959,26 @@ __device__ inline void iso(double ct, double ph, double out[3]) {
     out[2] = ct;
 }
 
-// Pairs of class cls (1: e-Cu, 2: Cu+-Cu), one thread per particle of the
-// charged species; each pair has one thread, so every particle is written by
-// at most one thread of the class.
+// Pairs of class cls (1: e-Cu, 2: Cu+-Cu, 3: e-Cu+ with Cu2+), one thread
+// per particle of the first species; each pair has one thread, so every
+// particle is written by at most one thread of the class.
 __global__ __launch_bounds__(kBlock) void k_pair(CollArgs a, int cls) {
-    const int sa = cls == 1 ? 0 : 1;
-    // one thread per grouped slot of the charged species, in slot order (its
+    const int sa = cls == 2 ? 1 : 0;
+    const int sb = cls == 3 ? 1 : 2;
+    // one thread per grouped slot of the first species, in slot order (its
     // own reads and writes coalesce), with its rank in the cell
     const int64_t pa0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (pa0 >= (int64_t)a.st->ngrp[sa]) return;
     const int32_t c = a.cellof[a.off[sa] + pa0];
     if (c < 0) return;
-    const int64_t NA = a.cnt[sa * a.nc + c], NB = a.cnt[2 * a.nc + c];
+    const int64_t NA = a.cnt[sa * a.nc + c], NB = a.cnt[sb * a.nc + c];
     if (NB == 0) return;
     const int64_t qa = a.crank[a.off[sa] + pa0];
-    const int64_t bB = a.start[2 * a.nc + c];
+    const int64_t bB = a.start[sb * a.nc + c];
     const bool a_proj = NA <= NB;
     const int64_t NT = a_proj ? NB : NA;
-    const double uc = draw2(a.seed, (uint32_t)c, a.step, cls == 1 ? pic::kTagPair1 : pic::kTagPair2, 0).a;
+    const uint32_t tag_pair = cls == 1 ? pic::kTagPair1 : (cls == 2 ? pic::kTagPair2 : kTagPairIon);
+    const double uc = draw2(a.seed, (uint32_t)c, a.step, tag_pair, 0).a;
     int64_t shift = (int64_t)floor(uc * (double)NT);
     if (shift > NT - 1) shift = NT - 1;
     uint32_t pb;
@@ -970,37 +991,46 @@ __global__ __launch_bounds__(kBlock) void k_pair(CollArgs a, int cls) {
     }
     const uint32_t pa = (uint32_t)pa0;
     if (cls == 2 && a.used[a.off[2] + pb]) return;
-    const uint32_t pid = a_proj ? a.id[sa][pa] : a.id[2][pb];
+    if (cls == 3 && (a.used[a.off[0] + pa] || a.used[a.off[1] + pb] || a.charge[pb] != 1)) return;
+    const uint32_t pid = a_proj ? a.id[sa][pa] : a.id[sb][pb];
     const double h = a.h, dt = a.dt;
     double* AV[3] = {a.vr[sa], a.vt[sa], a.vz[sa]};
-    double* BV[3] = {a.vr[2], a.vt[2], a.vz[2]};
+    double* BV[3] = {a.vr[sb], a.vt[sb], a.vz[sb]};
     const double vA[3] = {AV[0][pa], AV[1][pa], AV[2][pa]};
     const double vB[3] = {BV[0][pb], BV[1][pb], BV[2][pb]};
     const double u[3] = {(vA[0] - vB[0]) * h / dt, (vA[1] - vB[1]) * h / dt, (vA[2] - vB[2]) * h / dt};
     const double um = sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-    const double ma = cls == 1 ? kMe : a.m_ion, mb = a.m_ion;
+    const double ma = cls == 2 ? a.m_ion : kMe, mb = a.m_ion;
     const int i = c % (a.g.nr - 1);
     const double vol = kPi * (double)(2 * i + 1) * h * h * h;
     const double n = (double)NT / vol;
-    const Draw2 d = draw2(a.seed, pid, a.step, cls == 1 ? pic::kTagMcc1 : pic::kTagMcc2, 0);
+    const uint32_t tag = cls == 1 ? pic::kTagMcc1 : (cls == 2 ? pic::kTagMcc2 : kTagIon);
+    const Draw2 d = draw2(a.seed, pid, a.step, tag, 0);
     // the largest cross section of the class bounds P from above: a draw at
     // or above that bound is no collision, without the table look-ups
     if (!(d.a < -expm1(-um * n * a.sig_max[cls - 1] * dt))) return;
     const double E = 0.5 * ma * um * um / kQe;
-    double sig0, sig1 = 0.0;
+    double sig0, sig1 = 0.0, sig2 = 0.0;
     if (cls == 1) {
         sig0 = xs_at(a, 0, E);
         sig1 = E > a.xi ? xs_at(a, 1, E) : 0.0;
-    } else {
+        if (a.cu2) sig2 = E > a.xi + a.xi2 ? xs_at(a, 3, E) : 0.0;
+    } else if (cls == 2) {
         sig0 = xs_at(a, 2, E);
+    } else {
+        sig0 = E > a.xi2 ? xs_at(a, 4, E) : 0.0;
     }
-    const double stot = sig0 + sig1;
+    const double stot = a.cu2 && cls == 1 ? sig0 + sig1 + sig2 : sig0 + sig1;
     const double P = -expm1(-um * n * stot * dt);
     if (!(d.a < P)) return;
-    int proc = cls == 1 ? 1 : 0;
-    if (cls == 1 && d.b * stot < sig0) proc = 0;
+    int proc = 0;
+    if (cls == 1) {
+        if (d.b * stot < sig0) proc = 0;
+        else if (!a.cu2 || d.b * stot < sig0 + sig1) proc = 1;
+        else proc = 2;
+    }
     a.used[a.off[sa] + pa] = 1;
-    a.used[a.off[2] + pb] = 1;
+    a.used[a.off[sb] + pb] = 1;
     if (cls == 2) {
         for (int k = 0; k < 3; ++k) {
             AV[k][pa] = vB[k];
@@ -1009,7 +1039,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(CollArgs a, int cls) {
         atomicAdd(&a.st->events[3], 1ull);
         return;
     }
-    if (proc == 0) {
+    if (cls == 1 && proc == 0) {
         // Eq. du: R^-1(theta, phi) [R^-1(theta', phi') - I] (0, 0, |u|)
         const Draw2 r = draw2(a.seed, pid, a.step, pic::kTagMcc1, 1);
         const double ct2 = 2.0 * r.a - 1.0, ph2 = 2.0 * kPi * r.b;
@@ -1033,24 +1063,55 @@ __global__ __launch_bounds__(kBlock) void k_pair(CollArgs a, int cls) {
         atomicAdd(&a.st->events[1], 1ull);
         return;
     }
-    // impact ionization: in the neutral's frame the energy above xi is
-    // shared as U5 : 1 - U5, both electrons leave isotropically
-    const Draw2 r1 = draw2(a.seed, pid, a.step, pic::kTagMcc1, 1);
-    const Draw2 r2 = draw2(a.seed, pid, a.step, pic::kTagMcc1, 2);
-    const Draw2 r3 = draw2(a.seed, pid, a.step, pic::kTagMcc1, 3);
+    // ionizations: in the frame of the neutral (or ion) the energy above the
+    // threshold is shared by the electrons, each leaving isotropically
+    const Draw2 r1 = draw2(a.seed, pid, a.step, tag, 1);
+    const Draw2 r2 = draw2(a.seed, pid, a.step, tag, 2);
+    const Draw2 r3 = draw2(a.seed, pid, a.step, tag, 3);
     double s1[3], s2[3];
     iso(2.0 * r1.a - 1.0, 2.0 * kPi * r1.b, s1);
     iso(2.0 * r2.a - 1.0, 2.0 * kPi * r2.b, s2);
-    const double erem = E - a.xi;
-    const double e1 = r3.a * erem, e2 = erem - e1;
-    const double w1 = sqrt(2.0 * e1 * kQe / kMe), w2 = sqrt(2.0 * e2 * kQe / kMe);
     const double vn[3] = {vB[0] * h / dt, vB[1] * h / dt, vB[2] * h / dt};
+    if (cls == 3) {
+        // Cu+ + e -> Cu2+ + 2e above xi2; the ion keeps slot, id, velocity
+        const double rest3 = E - a.xi2;
+        const double g1 = r3.a * rest3, g2 = rest3 - g1;
+        const double v1 = sqrt(2.0 * g1 * kQe / kMe), v2 = sqrt(2.0 * g2 * kQe / kMe);
+        for (int k = 0; k < 3; ++k) {
+            AV[k][pa] = (vn[k] + v1 * s1[k]) * dt / h;
+            a.vei[3 * (int64_t)pb + k] = (vn[k] + v2 * s2[k]) * dt / h;
+        }
+        a.charge[pb] = 2;
+        a.iflag[pb] = 1;
+        atomicAdd(&a.st->events[6], 1ull);
+        return;
+    }
+    if (proc == 1) {
+        const double erem = E - a.xi;
+        const double e1 = r3.a * erem, e2 = erem - e1;
+        const double w1 = sqrt(2.0 * e1 * kQe / kMe), w2 = sqrt(2.0 * e2 * kQe / kMe);
+        for (int k = 0; k < 3; ++k) {
+            AV[k][pa] = (vn[k] + w1 * s1[k]) * dt / h;
+            a.ve[6 * (int64_t)pb + k] = (vn[k] + w2 * s2[k]) * dt / h;
+        }
+        a.pflag[pb] = 1;
+        atomicAdd(&a.st->events[2], 1ull);
+        return;
+    }
+    // Cu + e -> Cu2+ + 3e above xi + xi2: shares U5, U6 (1 - U5) and the rest
+    const Draw2 r4 = draw2(a.seed, pid, a.step, tag, 4);
+    double s3[3];
+    iso(2.0 * r4.a - 1.0, 2.0 * kPi * r4.b, s3);
+    const double rest = E - a.xi - a.xi2;
+    const double f1 = r3.a * rest, f2 = r3.b * (rest - f1), f3 = rest - f1 - f2;
+    const double w1 = sqrt(2.0 * f1 * kQe / kMe), w2 = sqrt(2.0 * f2 * kQe / kMe), w3 = sqrt(2.0 * f3 * kQe / kMe);
     for (int k = 0; k < 3; ++k) {
         AV[k][pa] = (vn[k] + w1 * s1[k]) * dt / h;
-        a.ve[3 * (int64_t)pb + k] = (vn[k] + w2 * s2[k]) * dt / h;
+        a.ve[6 * (int64_t)pb + k] = (vn[k] + w2 * s2[k]) * dt / h;
+        a.ve[6 * (int64_t)pb + 3 + k] = (vn[k] + w3 * s3[k]) * dt / h;
     }
-    a.pflag[pb] = 1;
-    atomicAdd(&a.st->events[2], 1ull);
+    a.pflag[pb] = 3;
+    atomicAdd(&a.st->events[5], 1ull);
 }
 
 __device__ inline double bilinear(const Geo& g, const double* f, int stride, int comp, double r, double z) {
@@ -1078,55 +1139,50 @@ __global__ __launch_bounds__(kBlock) void k_fi(CollArgs a) {
     }
 }
 
-// Per block of neutral slots: the impact (bcnt[b]) and field-ionization
-// (bcnt[nblk + b]) products; with the exclusive prefix of the concatenation
-// the r-th product of either kind follows in the required order.
-__device__ inline void block_flag_ranks(uint8_t f, uint32_t& rank, uint32_t tot[2]) {
-    __shared__ uint32_t wc[2][kBlock / 64];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const uint64_t m1 = __ballot(f == 1), m2 = __ballot(f == 2);
-    const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    if (lane == 0) {
-        wc[0][w] = (uint32_t)__popcll(m1);
-        wc[1][w] = (uint32_t)__popcll(m2);
+// Products in the order impact ionizations (entries 0 .. cap2 - 1, by
+// neutral slot), field ionizations (cap2 .. 2 cap2 - 1), ionizations of
+// Cu+ (2 cap2 .. 2 cap2 + cap1 - 1, by ion slot): the new ions and electrons
+// of every entry, whose exclusive prefixes give each product its slots and
+// ids (ids are taken in product order, the ion's first).
+__global__ __launch_bounds__(kBlock) void k_prod_counts(CollArgs a, int64_t L) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= L) return;
+    const int64_t c2 = a.cap[2];
+    uint32_t ni = 0, ne = 0;
+    if (e < 2 * c2) {
+        const int64_t p = e < c2 ? e : e - c2;
+        if (p < (int64_t)a.st->n[2]) {
+            const uint8_t f = a.pflag[p];
+            if (e < c2 && (f == 1 || f == 3)) {
+                ni = 1;
+                ne = f == 3 ? 2 : 1;
+            } else if (e >= c2 && f == 2) {
+                ni = 1;
+                ne = 1;
+            }
+        }
+    } else {
+        const int64_t p = e - 2 * c2;
+        if (p < (int64_t)a.st->n[1] && a.iflag[p]) ne = 1;
     }
-    __syncthreads();
-    uint32_t pre[2] = {0, 0};
-    tot[0] = tot[1] = 0;
-    for (int q = 0; q < kBlock / 64; ++q) {
-        pre[0] += q < w ? wc[0][q] : 0u;
-        pre[1] += q < w ? wc[1][q] : 0u;
-        tot[0] += wc[0][q];
-        tot[1] += wc[1][q];
-    }
-    rank = f == 1 ? pre[0] + (uint32_t)__popcll(m1 & lt) : pre[1] + (uint32_t)__popcll(m2 & lt);
+    a.pci[e] = ni;
+    a.pce[e] = ne;
 }
 
-__global__ __launch_bounds__(kBlock) void k_prod_count(CollArgs a) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint8_t f = p < (int64_t)a.st->n[2] ? a.pflag[p] : 0;
-    uint32_t rank, tot[2];
-    block_flag_ranks(f, rank, tot);
-    if (threadIdx.x == 0) {
-        a.bcnt[blockIdx.x] = tot[0];
-        a.bcnt[a.nblk + blockIdx.x] = tot[1];
-    }
-}
-
-// room for T new electrons and ions with 2 T ids (kind 0), or T electrons
-// with T ids (kind 1: emission)
-__global__ void k_commit(State* st, int kind, int64_t cap0, int64_t cap1) {
+// room for the products' ions and electrons and their ids
+__global__ void k_prod_commit(CollArgs a, int64_t L) {
     if (threadIdx.x != 0) return;
-    const unsigned long long T = st->total;
+    State* st = a.st;
     st->skip = 0;
-    if (T == 0) return;
-    const unsigned long long ids = kind == 0 ? 2 * T : T;
-    if (st->n[0] + T > (unsigned long long)cap0 || (kind == 0 && st->n[1] + T > (unsigned long long)cap1)) {
+    const unsigned long long TI = L ? (unsigned long long)a.ppi[L - 1] + a.pci[L - 1] : 0ull;
+    const unsigned long long TE = L ? (unsigned long long)a.ppe[L - 1] + a.pce[L - 1] : 0ull;
+    if (TI + TE == 0) return;
+    if (st->n[0] + TE > (unsigned long long)a.cap[0] || st->n[1] + TI > (unsigned long long)a.cap[1]) {
         st->skip = 1;
         if (st->error == 0) st->error = PIC_E_CAPACITY;
         return;
     }
-    if (st->next_id + ids > (unsigned long long)kDead) {
+    if (st->next_id + TI + TE > (unsigned long long)kDead) {
         st->skip = 1;
         if (st->error == 0) st->error = PIC_E_OVERFLOW;
         return;
@@ -1134,40 +1190,79 @@ __global__ void k_commit(State* st, int kind, int64_t cap0, int64_t cap1) {
     st->base_n[0] = st->n[0];
     st->base_n[1] = st->n[1];
     st->base_id = st->next_id;
-    st->n[0] += T;
-    if (kind == 0) st->n[1] += T;
-    st->next_id += ids;
-    if (kind == 1) st->injected += T;
+    st->n[0] += TE;
+    st->n[1] += TI;
+    st->next_id += TI + TE;
 }
 
-__global__ __launch_bounds__(kBlock) void k_prod_place(CollArgs a) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint8_t f = p < (int64_t)a.st->n[2] ? a.pflag[p] : 0;
-    uint32_t rank, tot[2];
-    block_flag_ranks(f, rank, tot);
-    if (f == 0 || a.st->skip) return;
-    const uint64_t r = (uint64_t)a.bpre[(f == 1 ? 0 : a.nblk) + blockIdx.x] + rank;
-    const uint64_t si = a.st->base_n[1] + r, se = a.st->base_n[0] + r;
-    const uint32_t idi = (uint32_t)(a.st->base_id + 2 * r);
+__global__ __launch_bounds__(kBlock) void k_prod_place(CollArgs a, int64_t L) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= L || a.st->skip) return;
+    const uint32_t ni = a.pci[e], ne = a.pce[e];
+    if (ni + ne == 0) return;
+    const uint64_t oi = a.ppi[e], oe = a.ppe[e];
+    const uint64_t id0 = a.st->base_id + oi + oe;
+    const uint64_t se = a.st->base_n[0] + oe;
+    const int64_t c2 = a.cap[2];
+    if (e >= 2 * c2) {
+        // ionization of Cu+: one electron at the ion
+        const int64_t p = e - 2 * c2;
+        a.r[0][se] = a.r[1][p];
+        a.z[0][se] = a.z[1][p];
+        a.vr[0][se] = a.vei[3 * p];
+        a.vt[0][se] = a.vei[3 * p + 1];
+        a.vz[0][se] = a.vei[3 * p + 2];
+        a.id[0][se] = (uint32_t)id0;
+        return;
+    }
+    const int64_t p = e < c2 ? e : e - c2;
+    const uint8_t f = a.pflag[p];
+    const uint64_t si = a.st->base_n[1] + oi;
     a.r[1][si] = a.r[2][p];
     a.z[1][si] = a.z[2][p];
     a.vr[1][si] = a.vr[2][p];
     a.vt[1][si] = a.vt[2][p];
     a.vz[1][si] = a.vz[2][p];
-    a.id[1][si] = idi;
-    a.r[0][se] = a.r[2][p];
-    a.z[0][se] = a.z[2][p];
-    if (f == 1) {
-        a.vr[0][se] = a.ve[3 * p];
-        a.vt[0][se] = a.ve[3 * p + 1];
-        a.vz[0][se] = a.ve[3 * p + 2];
-    } else {
-        a.vr[0][se] = a.vr[2][p];
-        a.vt[0][se] = a.vt[2][p];
-        a.vz[0][se] = a.vz[2][p];
+    a.id[1][si] = (uint32_t)id0;
+    if (a.charge) a.charge[si] = f == 3 ? 2 : 1;
+    for (uint32_t q = 0; q < ne; ++q) {
+        a.r[0][se + q] = a.r[2][p];
+        a.z[0][se + q] = a.z[2][p];
+        if (f == 2) {
+            a.vr[0][se + q] = a.vr[2][p];
+            a.vt[0][se + q] = a.vt[2][p];
+            a.vz[0][se + q] = a.vz[2][p];
+        } else {
+            a.vr[0][se + q] = a.ve[6 * p + 3 * q];
+            a.vt[0][se + q] = a.ve[6 * p + 3 * q + 1];
+            a.vz[0][se + q] = a.ve[6 * p + 3 * q + 2];
+        }
+        a.id[0][se + q] = (uint32_t)(id0 + 1 + q);
     }
-    a.id[0][se] = idi + 1u;
     a.id[2][p] = kDead;
+}
+
+// room for the T = st->total emitted electrons and their ids
+__global__ void k_emit_commit(State* st, int64_t cap0) {
+    if (threadIdx.x != 0) return;
+    const unsigned long long T = st->total;
+    st->skip = 0;
+    if (T == 0) return;
+    if (st->n[0] + T > (unsigned long long)cap0) {
+        st->skip = 1;
+        if (st->error == 0) st->error = PIC_E_CAPACITY;
+        return;
+    }
+    if (st->next_id + T > (unsigned long long)kDead) {
+        st->skip = 1;
+        if (st->error == 0) st->error = PIC_E_OVERFLOW;
+        return;
+    }
+    st->base_n[0] = st->n[0];
+    st->base_id = st->next_id;
+    st->n[0] += T;
+    st->next_id += T;
+    st->injected += T;
 }
 
 // ---------------------------------------------------------------------------
@@ -1313,8 +1408,10 @@ struct Work {
     int32_t* cellof = nullptr;
     uint8_t* used = nullptr;
     uint8_t* pflag = nullptr;  // cap[2]
-    double* ve = nullptr;      // 3 cap[2]
-    uint32_t *bcnt = nullptr, *bpre = nullptr;  // 2 nblk each
+    double* ve = nullptr;      // 6 cap[2]
+    uint8_t* iflag = nullptr;  // cap[1]
+    double* vei = nullptr;     // 3 cap[1]
+    uint32_t *pci = nullptr, *pce = nullptr, *ppi = nullptr, *ppe = nullptr;  // 2 cap[2] + cap[1] each
     uint32_t* pcnt = nullptr;                   // patches
     uint64_t* poff = nullptr;
     double* z = nullptr;                        // preconditioned residual (nodes)
@@ -1328,7 +1425,7 @@ size_t layout(const pic_rz_config* c, const int64_t cap[3], char* base, Work* w)
     const size_t nn = (size_t)c->nr * c->nz;
     const size_t nc = (size_t)(c->nr - 1) * (c->nz - 1);
     const size_t ncap = (size_t)(cap[0] + cap[1] + cap[2]);
-    const size_t nblk = (size_t)((cap[2] + kBlock - 1) / kBlock);
+    const size_t nprod = (size_t)(2 * cap[2] + cap[1]);
     const size_t np = (size_t)patches(c);
     size_t off = 0;
     auto take = [&](size_t b) -> char* {
@@ -1347,7 +1444,7 @@ size_t layout(const pic_rz_config* c, const int64_t cap[3], char* base, Work* w)
     t.start = (uint32_t*)take(3 * nc * 4);
     t.cpos = (uint32_t*)take(ncap * 4);
     t.crank = (uint32_t*)take(ncap * 4);
-    const size_t nscan = std::max(3 * nc, 2 * nblk) / kScanChunk + 2;
+    const size_t nscan = std::max(3 * nc, nprod) / kScanChunk + 2;
     t.ssum = (uint32_t*)take(nscan * 4);
     t.spre = (uint32_t*)take(nscan * 4);
     t.seg = (uint32_t*)take(ncap * 4);
@@ -1356,9 +1453,13 @@ size_t layout(const pic_rz_config* c, const int64_t cap[3], char* base, Work* w)
     t.cellof = (int32_t*)take(ncap * 4);
     t.used = (uint8_t*)take(ncap);
     t.pflag = (uint8_t*)take((size_t)cap[2]);
-    t.ve = (double*)take((size_t)cap[2] * 24);
-    t.bcnt = (uint32_t*)take(2 * nblk * 4);
-    t.bpre = (uint32_t*)take(2 * nblk * 4);
+    t.ve = (double*)take((size_t)cap[2] * 48);
+    t.iflag = (uint8_t*)take((size_t)cap[1]);
+    t.vei = (double*)take((size_t)cap[1] * 24);
+    t.pci = (uint32_t*)take(nprod * 4 + 4);
+    t.pce = (uint32_t*)take(nprod * 4 + 4);
+    t.ppi = (uint32_t*)take(nprod * 4 + 4);
+    t.ppe = (uint32_t*)take(nprod * 4 + 4);
     t.pcnt = (uint32_t*)take(np * 4 + 4);
     t.poff = (uint64_t*)take(np * 8 + 8);
     t.z = (double*)take(nn * 8);
@@ -1391,6 +1492,8 @@ const char* check(const pic_rz_config* c) {
     if (c->xs_n > 0 && !(c->xs_emin > 0 && c->xs_emax > c->xs_emin && c->xi > 0))
         return "collisions need 0 < xs_emin < xs_emax and xi > 0";
     if (c->fn_rings < 0 || c->fn_rings > (1 << 20)) return "fn_rings out of range";
+    if (c->cu2 != 0 && c->cu2 != 1) return "cu2 must be 0 or 1";
+    if (c->cu2 && !(c->xs_n > 0 && c->xi2 > 0)) return "Cu2+ needs the five tables and xi2 > 0";
     if (c->fn_rings > 0 && !(c->phi_w > 0 && c->tip_r > 0)) return "emission needs phi_w > 0 and a tip";
     return nullptr;
 }
@@ -1416,7 +1519,7 @@ struct pic_rz_ctx {
     double V0 = 0.0, F1 = 0.0;
     int64_t step = 0;
     int last_iters = 0;
-    double sig_max[2] = {0.0, 0.0};  // bounds of the class cross sections, from the tables
+    double sig_max[3] = {0.0, 0.0, 0.0};  // bounds of the class cross sections, from the tables
     // two PCG iterations of the step solve (phi = buf.phi) as one graph
     hipStream_t cap_stream = nullptr;
     hipGraph_t pcg_graph = nullptr;
@@ -1634,16 +1737,21 @@ CollArgs coll_args(pic_rz_ctx* c, uint32_t step) {
     a.used = c->w.used;
     a.pflag = c->w.pflag;
     a.ve = c->w.ve;
-    a.bcnt = c->w.bcnt;
-    a.bpre = c->w.bpre;
-    a.nblk = (c->buf.cap[2] + kBlock - 1) / kBlock;
+    a.iflag = c->w.iflag;
+    a.vei = c->w.vei;
+    a.charge = c->cfg.cu2 ? c->buf.charge : nullptr;
+    a.pci = c->w.pci;
+    a.pce = c->w.pce;
+    a.ppi = c->w.ppi;
+    a.ppe = c->w.ppe;
+    a.cu2 = c->cfg.cu2;
+    a.xi2 = c->cfg.xi2;
     a.E = c->buf.field;
     a.xs = c->buf.xs;
     a.xs_n = c->cfg.xs_n;
     a.xs_emin = c->cfg.xs_emin;
     a.xs_lnr = std::log(c->cfg.xs_emax / c->cfg.xs_emin);
-    a.sig_max[0] = c->sig_max[0];
-    a.sig_max[1] = c->sig_max[1];
+    for (int k = 0; k < 3; ++k) a.sig_max[k] = c->sig_max[k];
     a.h = c->cfg.h;
     a.dt = c->cfg.dt;
     a.m_ion = c->cfg.m_ion;
@@ -1692,12 +1800,16 @@ void collide(pic_rz_ctx* c, uint32_t step) {
         hipLaunchKernelGGL(k_pair, dim3(grid_of(c->buf.cap[0])), dim3(kBlock), 0, c->stream, a, 1);
     if (c->buf.cap[1] > 0)
         hipLaunchKernelGGL(k_pair, dim3(grid_of(c->buf.cap[1])), dim3(kBlock), 0, c->stream, a, 2);
-    if (c->buf.cap[2] == 0) return;
-    hipLaunchKernelGGL(k_fi, dim3(grid_of(c->buf.cap[2])), dim3(kBlock), 0, c->stream, a);
-    hipLaunchKernelGGL(k_prod_count, dim3((unsigned)a.nblk), dim3(kBlock), 0, c->stream, a);
-    scan_u32(c, a.bcnt, a.bpre, 2 * a.nblk);
-    hipLaunchKernelGGL(k_commit, dim3(1), dim3(64), 0, c->stream, c->st, 0, c->buf.cap[0], c->buf.cap[1]);
-    hipLaunchKernelGGL(k_prod_place, dim3((unsigned)a.nblk), dim3(kBlock), 0, c->stream, a);
+    if (c->cfg.cu2 && c->buf.cap[0] > 0 && c->buf.cap[1] > 0)
+        hipLaunchKernelGGL(k_pair, dim3(grid_of(c->buf.cap[0])), dim3(kBlock), 0, c->stream, a, 3);
+    if (c->buf.cap[2] > 0) hipLaunchKernelGGL(k_fi, dim3(grid_of(c->buf.cap[2])), dim3(kBlock), 0, c->stream, a);
+    const int64_t L = 2 * c->buf.cap[2] + c->buf.cap[1];
+    if (L == 0) return;
+    hipLaunchKernelGGL(k_prod_counts, dim3(grid_of(L)), dim3(kBlock), 0, c->stream, a, L);
+    scan_u32(c, a.pci, a.ppi, L);
+    scan_u32(c, a.pce, a.ppe, L);
+    hipLaunchKernelGGL(k_prod_commit, dim3(1), dim3(64), 0, c->stream, a, L);
+    hipLaunchKernelGGL(k_prod_place, dim3(grid_of(L)), dim3(kBlock), 0, c->stream, a, L);
 }
 
 // Fowler-Nordheim emission from the rings of the tip
@@ -1730,7 +1842,7 @@ void emit(pic_rz_ctx* c, uint32_t step) {
     hipLaunchKernelGGL(k_emit_count, dim3(grid_of(a.npatch)), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(k_scan<uint64_t>, dim3(1), dim3(kScanBlock), 0, c->stream, (const uint32_t*)a.cnt, a.offs,
                        a.npatch, c->st);
-    hipLaunchKernelGGL(k_commit, dim3(1), dim3(64), 0, c->stream, c->st, 1, c->buf.cap[0], c->buf.cap[1]);
+    hipLaunchKernelGGL(k_emit_commit, dim3(1), dim3(64), 0, c->stream, c->st, c->buf.cap[0]);
     hipLaunchKernelGGL(k_emit_place, dim3((unsigned)a.npatch), dim3(kBlock), 0, c->stream, a);
 }
 
@@ -1753,6 +1865,7 @@ pic_status pic_rz_init(const pic_rz_config* cfg, const pic_rz_buffers* bufs, voi
     if (!caps_ok(bufs->cap) || bufs->scratch_bytes < layout(cfg, bufs->cap, nullptr, nullptr))
         return PIC_E_INVALID_ARG;
     if (cfg->xs_n > 0 && !bufs->xs) return PIC_E_INVALID_ARG;
+    if (cfg->cu2 && bufs->cap[1] > 0 && !bufs->charge) return PIC_E_INVALID_ARG;
     for (int s = 0; s < 3; ++s) {
         if (bufs->n[s] < 0 || bufs->n[s] > bufs->cap[s]) return PIC_E_INVALID_ARG;
         if (bufs->cap[s] > 0 && (!bufs->r[s] || !bufs->z[s] || !bufs->vr[s] || !bufs->vt[s] || !bufs->vz[s] ||
@@ -1773,17 +1886,18 @@ pic_status pic_rz_init(const pic_rz_config* cfg, const pic_rz_buffers* bufs, voi
     c->mg = mg_dims(cfg->nr, cfg->nz);
     if (cfg->xs_n > 0) {
         // an interpolated value exceeds the largest node at most by rounding
-        std::vector<double> t((size_t)3 * cfg->xs_n);
+        const int ntab = cfg->cu2 ? 5 : 3, n = cfg->xs_n;
+        std::vector<double> t((size_t)ntab * n);
         if (hipMemcpy(t.data(), bufs->xs, t.size() * 8, hipMemcpyDeviceToHost) != hipSuccess) {
             delete c;
             return PIC_E_HIP;
         }
-        for (int k = 0; k < cfg->xs_n; ++k) {
-            c->sig_max[0] = std::max(c->sig_max[0], t[k] + t[cfg->xs_n + k]);
-            c->sig_max[1] = std::max(c->sig_max[1], t[2 * cfg->xs_n + k]);
+        for (int k = 0; k < n; ++k) {
+            c->sig_max[0] = std::max(c->sig_max[0], t[k] + t[n + k] + (cfg->cu2 ? t[3 * n + k] : 0.0));
+            c->sig_max[1] = std::max(c->sig_max[1], t[2 * n + k]);
+            if (cfg->cu2) c->sig_max[2] = std::max(c->sig_max[2], t[4 * n + k]);
         }
-        c->sig_max[0] *= 1.0 + 1e-12;
-        c->sig_max[1] *= 1.0 + 1e-12;
+        for (int k = 0; k < 3; ++k) c->sig_max[k] *= 1.0 + 1e-12;
     }
     c->st = c->w.st;
     c->r = c->w.r;
@@ -1799,6 +1913,9 @@ pic_status pic_rz_init(const pic_rz_config* cfg, const pic_rz_buffers* bufs, voi
         if (bufs->n[sp] > 0)
             hipLaunchKernelGGL(k_check_ids, dim3(grid_of(bufs->n[sp])), dim3(kBlock), 0, c->stream, bufs->id[sp],
                                bufs->n[sp], c->st);
+    if (s == PIC_OK && cfg->cu2 && bufs->n[1] > 0)
+        hipLaunchKernelGGL(k_check_charge, dim3(grid_of(bufs->n[1])), dim3(kBlock), 0, c->stream,
+                           (const uint8_t*)bufs->charge, bufs->n[1], c->st);
     if (s == PIC_OK) {
         State h1{};
         s = hip_ok(c, hipMemcpyAsync(&h1, c->st, sizeof(State), hipMemcpyDeviceToHost, c->stream), "copy");
@@ -1899,6 +2016,7 @@ pic_status pic_rz_step(pic_rz_ctx* c, int32_t nsteps, uint32_t flags) {
                 a.vt = c->buf.vt[s];
                 a.vz = c->buf.vz[s];
                 a.id = c->buf.id[s];
+                a.charge = (s == 1 && c->cfg.cu2) ? c->buf.charge : nullptr;
                 a.E = c->buf.field;
                 a.kq = qm[s] * c->cfg.dt * c->cfg.dt / c->cfg.h;
                 a.sp = s;
@@ -1920,7 +2038,8 @@ pic_status pic_rz_step(pic_rz_ctx* c, int32_t nsteps, uint32_t flags) {
                 if (cap[s] > 0)
                     hipLaunchKernelGGL(k_deposit, dim3(grid_of(cap[s])), dim3(kBlock), 0, c->stream, c->g,
                                        c->buf.r[s], c->buf.z[s], c->buf.id[s], (const State*)c->st, s,
-                                       (int64_t)(s == 0 ? -1 : 1), c->buf.rho, grouped);
+                                       (int64_t)(s == 0 ? -1 : 1), c->buf.rho, grouped,
+                                       (const uint8_t*)((s == 1 && c->cfg.cu2) ? c->buf.charge : nullptr));
         }
         pic_status st = hip_ok(c, hipGetLastError(), "step");
         if (st != PIC_OK) return st;
@@ -1953,7 +2072,12 @@ pic_status pic_rz_moments(pic_rz_ctx* c, pic_rz_moments_t* out) {
     for (int sp = 0; sp < 3; ++sp)
         if (c->buf.cap[sp] > 0)
             hipLaunchKernelGGL(k_counts, dim3(std::min<unsigned>(1024u, grid_of(c->buf.cap[sp]))), dim3(kBlock), 0,
-                               c->stream, c->buf.id[sp], (const State*)c->st, sp, c->cnt + sp);
+                               c->stream, c->buf.id[sp], (const State*)c->st, sp, c->cnt + sp,
+                               (const uint8_t*)nullptr);
+    if (c->cfg.cu2 && c->buf.cap[1] > 0)
+        hipLaunchKernelGGL(k_counts, dim3(std::min<unsigned>(1024u, grid_of(c->buf.cap[1]))), dim3(kBlock), 0,
+                           c->stream, c->buf.id[1], (const State*)c->st, 1, c->cnt + 4,
+                           (const uint8_t*)c->buf.charge);
     const int64_t nn = (int64_t)c->g.nr * c->g.nz;
     hipLaunchKernelGGL(k_qsum, dim3(256), dim3(kBlock), 0, c->stream, c->buf.rho, nn, c->cnt + 3);
     unsigned long long h[8];
@@ -1977,6 +2101,9 @@ pic_status pic_rz_moments(pic_rz_ctx* c, pic_rz_moments_t* out) {
     for (int k = 0; k < 5; ++k) out->events[k] = (int64_t)st.events[k];
     out->injected = (int64_t)st.injected;
     out->next_id = (int64_t)st.next_id;
+    out->double_ionizations = (int64_t)st.events[5];
+    out->ion_ionizations = (int64_t)st.events[6];
+    out->n_cu2 = (int64_t)h[4];
     return PIC_OK;
 }
 

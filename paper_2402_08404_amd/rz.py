@@ -23,21 +23,23 @@ class pic_rz_config(C.Structure):
                 ("tip_h", C.c_double), ("apex_field", C.c_double), ("dt", C.c_double), ("m_ion", C.c_double),
                 ("laplace_rtol", C.c_double), ("maxit", C.c_int32), ("reserved", C.c_int32),
                 ("step_rtol", C.c_double), ("seed", C.c_uint64), ("xi", C.c_double), ("phi_w", C.c_double),
-                ("xs_emin", C.c_double), ("xs_emax", C.c_double), ("xs_n", C.c_int32), ("fn_rings", C.c_int32)]
+                ("xs_emin", C.c_double), ("xs_emax", C.c_double), ("xs_n", C.c_int32), ("fn_rings", C.c_int32),
+                ("cu2", C.c_int32), ("reserved3", C.c_int32), ("xi2", C.c_double)]
 
 
 class pic_rz_buffers(C.Structure):
     _fields_ = [(k, C.c_void_p * 3) for k in ("r", "z", "vr", "vt", "vz", "id")] + \
                [("cap", C.c_int64 * 3), ("n", C.c_int64 * 3), ("phi", C.c_void_p), ("phi1", C.c_void_p),
                 ("rho", C.c_void_p), ("field", C.c_void_p), ("node_type", C.c_void_p), ("scratch", C.c_void_p),
-                ("scratch_bytes", C.c_size_t), ("xs", C.c_void_p)]
+                ("scratch_bytes", C.c_size_t), ("xs", C.c_void_p), ("charge", C.c_void_p)]
 
 
 class pic_rz_moments_t(C.Structure):
     _fields_ = [("n_alive", C.c_int64 * 3), ("absorbed", (C.c_int64 * 5) * 3), ("q_total", C.c_int64),
                 ("step", C.c_int64), ("v0", C.c_double), ("apex_field1", C.c_double),
                 ("last_cg_iters", C.c_int32), ("error", C.c_int32), ("n_slots", C.c_int64 * 3),
-                ("events", C.c_int64 * 5), ("injected", C.c_int64), ("next_id", C.c_int64)]
+                ("events", C.c_int64 * 5), ("injected", C.c_int64), ("next_id", C.c_int64),
+                ("double_ionizations", C.c_int64), ("ion_ionizations", C.c_int64), ("n_cu2", C.c_int64)]
 
 
 _bound = False
@@ -97,28 +99,33 @@ def pic_rz_moments(ctx) -> dict:
     return {"n_alive": np.array(m.n_alive[:]), "absorbed": np.array([list(r) for r in m.absorbed]),
             "q_total": m.q_total, "step": m.step, "v0": m.v0, "apex_field1": m.apex_field1,
             "last_cg_iters": m.last_cg_iters, "error": m.error, "n_slots": np.array(m.n_slots[:]),
-            "events": np.array(m.events[:]), "injected": m.injected, "next_id": m.next_id}
+            "events": np.array(list(m.events[:]) + [m.double_ionizations, m.ion_ionizations]),
+            "injected": m.injected, "next_id": m.next_id, "n_cu2": m.n_cu2}
 
 
 class RZSimulation:
     """One axisymmetric instance on a GPU. load: dict species index ->
     dict r, z, vr, vt, vz (grid units, FP64); particles are numbered in load
     order (species 0, 1, 2) unless ids (species -> uint32 array) is given.
-    xs: (emin, emax, elastic, ionization, charge exchange) cross-section
-    tables for the collisions; fn_rings > 0 enables the emission."""
+    xs: (emin, emax, elastic, ionization, charge exchange[, double
+    ionization, ionization of Cu+]) cross-section tables for the collisions;
+    fn_rings > 0 enables the emission; cu2 adds Cu2+ as an ion charge state
+    (load[1]["q"] gives the initial states)."""
 
     def __init__(self, nr, nz, h, tip_r, tip_h, apex_field, dt, m_ion, load, caps=None, laplace_rtol=1e-13,
                  step_rtol=1e-10, maxit=100000, device="cuda", seed=1, xs=None, xi=7.726380, phi_w=4.5,
-                 fn_rings=0, ids=None):
+                 fn_rings=0, ids=None, cu2=False, xi2=20.29239):
         self.device = torch.device(device)
         self.cfg = pic_rz_config(nr=nr, nz=nz, h=h, tip_r=tip_r, tip_h=tip_h, apex_field=apex_field, dt=dt,
                                  m_ion=m_ion, laplace_rtol=laplace_rtol, maxit=maxit, step_rtol=step_rtol,
-                                 seed=seed, xi=xi, phi_w=phi_w, fn_rings=fn_rings)
+                                 seed=seed, xi=xi, phi_w=phi_w, fn_rings=fn_rings, cu2=1 if cu2 else 0, xi2=xi2)
         self.xs = None
         if xs is not None:
             self.cfg.xs_emin, self.cfg.xs_emax = xs[0], xs[1]
             self.cfg.xs_n = len(xs[2])
-            self.xs = torch.as_tensor(np.concatenate([np.asarray(t, np.float64) for t in xs[2:5]])).to(self.device)
+            ntab = 5 if cu2 else 3
+            self.xs = torch.as_tensor(np.concatenate([np.asarray(t, np.float64) for t in xs[2:2 + ntab]])).to(
+                self.device)
         n = [len(load[s]["r"]) if s in load else 0 for s in range(3)]
         caps = caps or [max(k, 1) for k in n]
         self.sp = []
@@ -156,6 +163,12 @@ class RZSimulation:
             setattr(b, k, getattr(self, k).data_ptr())
         b.scratch_bytes = sb + 256
         b.xs = self.xs.data_ptr() if self.xs is not None else None
+        self.charge = None
+        if cu2:
+            self.charge = torch.ones(max(caps[1], 1), dtype=torch.uint8, device=self.device)
+            if n[1] and "q" in load[1]:
+                self.charge[: n[1]] = torch.as_tensor(np.asarray(load[1]["q"], np.uint8))
+            b.charge = self.charge.data_ptr()
         self.bufs = b
         self.n = n
         torch.cuda.synchronize(self.device)
@@ -179,6 +192,8 @@ class RZSimulation:
             alive = ids != DEAD
             d = {k: self.sp[s][k][: n[s]].cpu().numpy()[alive] for k in ("r", "z", "vr", "vt", "vz")}
             d["id"] = ids[alive]
+            if s == 1 and self.charge is not None:
+                d["q"] = self.charge[: n[s]].cpu().numpy()[alive]
             out.append(d)
         return out
 

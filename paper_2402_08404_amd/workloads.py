@@ -93,6 +93,22 @@ def synthetic_tables(n: int = 256, emin: float = 1e-2, emax: float = 1e4, xi: fl
     return el, iz, cx
 
 
+CU_XI2_EV = 20.29239     # second ionization energy of Cu [eV] (NIST ASD)
+
+
+def synthetic_tables_cu2(n: int = 256, emin: float = 1e-2, emax: float = 1e4, xi: float = CU_XI_EV,
+                         xi2: float = CU_XI2_EV):
+    """The two Cu2+ processes in the same Lotz form as the single ionization
+    (their measured cross sections are cited, not given): Cu + e -> Cu2+ +
+    3e above xi + xi2 at a tenth of that form's height, and Cu+ + e -> Cu2+ +
+    2e above xi2, in m^2 on n log-spaced energies."""
+    E = emin * (emax / emin) ** (np.arange(n) / (n - 1))
+    x2 = xi + xi2
+    iz2 = np.where(E > x2, 0.45e-18 * np.log(np.maximum(E, x2) / x2) / (E * x2), 0.0)
+    izi = np.where(E > xi2, 4.5e-18 * np.log(np.maximum(E, xi2) / xi2) / (E * xi2), 0.0)
+    return iz2, izi
+
+
 def _with_tables(cfg: Config, tabs) -> Config:
     cfg.xs_el, cfg.xs_iz, cfg.xs_cx = (np.ascontiguousarray(t, dtype=np.float64) for t in tabs)
     return cfg

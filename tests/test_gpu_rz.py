@@ -141,11 +141,16 @@ def _tables(scale=1e4):
     return (1e-2, 1e4, el * scale, iz * scale, cx * scale)
 
 
-def _pair_all(seed=1, n=(3000, 1500, 6000), apex=10e9, xs=True, fn_rings=0, caps=None, load=None):
+def _tables_cu2(scale=1e4):
+    iz2, izi = W.synthetic_tables_cu2()
+    return _tables(scale) + (iz2 * scale, izi * scale)
+
+
+def _pair_all(seed=1, n=(3000, 1500, 6000), apex=10e9, xs=True, fn_rings=0, caps=None, load=None, cu2=False):
     geom = dict(GEOM, apex_field=apex)
-    tabs = _tables() if xs else None
+    tabs = (_tables_cu2() if cu2 else _tables()) if xs else None
     o = RZ(geom["nr"], geom["nz"], geom["h"], geom["tip_r"], geom["tip_h"], geom["apex_field"], geom["dt"],
-           geom["m_ion"], seed=seed, xs=tabs, fn_rings=fn_rings or 16)
+           geom["m_ion"], seed=seed, xs=tabs, fn_rings=fn_rings or 16, cu2=cu2)
     if load is None:
         load = _load(o, np.random.default_rng(seed), n)
     nid = 0
@@ -158,7 +163,7 @@ def _pair_all(seed=1, n=(3000, 1500, 6000), apex=10e9, xs=True, fn_rings=0, caps
         cnt = [len(load[s]["r"]) if s in load else 0 for s in range(3)]
         caps = [cnt[0] + cnt[2] + 4096, cnt[1] + cnt[2] + 1, cnt[2] + 1]
     g = rz.RZSimulation(**geom, load=load, laplace_rtol=1e-13, step_rtol=1e-14, seed=seed, xs=tabs,
-                        fn_rings=fn_rings, caps=caps)
+                        fn_rings=fn_rings, caps=caps, cu2=cu2)
     g.set_phi(o.phi)
     return g, o
 
@@ -176,6 +181,8 @@ def _compare_all(g, o, tol):
             d = np.abs(a[k] - b[k])
             scale = np.abs(b[k]) + 1e-3 * (np.abs(b[k]).max() if len(b[k]) else 0.0) + 1e-300
             assert (d <= tol * scale).all(), (s, k, (d / scale).max())
+        if "q" in a:
+            assert np.array_equal(a["q"], b["q"]), s
 
 
 def test_rz_collide_parity():
@@ -320,3 +327,56 @@ def test_rz_multigrid_levels_solve():
     assert info["converged"] and info["iterations"] <= 20, info
     phi = g.grid("phi")
     assert np.abs(phi - o.phi).max() <= 1e-9 * np.abs(o.phi).max()
+
+
+def _load_cu2(seed, n=(3000, 1500, 6000)):
+    o0 = RZ(GEOM["nr"], GEOM["nz"], GEOM["h"], GEOM["tip_r"], GEOM["tip_h"], GEOM["apex_field"], GEOM["dt"],
+            GEOM["m_ion"])
+    rng = np.random.default_rng(seed)
+    load = _load(o0, rng, n)
+    # electrons fast enough for both Cu2+ processes, a third of the ions Cu2+
+    for k in ("vr", "vt", "vz"):
+        load[0][k] = rng.normal(0, 0.08, len(load[0]["r"]))
+    q = np.ones(len(load[1]["r"]), np.uint8)
+    q[::3] = 2
+    load[1]["q"] = q
+    return load
+
+
+def test_rz_cu2_collide_parity():
+    """Cu2+ as an ion charge state: four collision stages with every process
+    (double ionization of Cu, ionization of Cu+), states, charge states,
+    events and products by id."""
+    print("case: rz Cu2+ collide", flush=True)
+    g, o = _pair_all(seed=23, load=_load_cu2(23), cu2=True)
+    for step in range(4):
+        g.step(1, rz.PIC_RZ_COLLIDE | rz.PIC_RZ_ADVANCE)
+        o.collide()
+        o.step_no += 1
+        _compare_all(g, o, 1e-12)
+        m = g.moments()
+        assert np.array_equal(m["events"], o.events), (m["events"], o.events)
+        assert m["next_id"] == o.next_id
+        assert m["n_cu2"] == int((o.sp[1]["q"] == 2).sum())
+    assert o.events[5] > 5 and o.events[6] > 20 and o.events[2] > 20, o.events
+
+
+def test_rz_cu2_all_stages_steps():
+    """Eight whole steps with Cu2+: the doubled kick and deposit of Cu2+,
+    node charge bit-exact, particles and events as the oracle's."""
+    print("case: rz Cu2+ all stages", flush=True)
+    g, o = _pair_all(seed=29, load=_load_cu2(29, (4000, 1500, 8000)), apex=14e9, fn_rings=16, cu2=True,
+                     caps=[40000, 20000, 8000])
+    g.step(1, rz.PIC_RZ_DEPOSIT | rz.PIC_RZ_SOLVE)
+    o.deposit()
+    o.solve()
+    assert np.array_equal(g.grid("rho"), o.Q)
+    for s in range(8):
+        g.step(1, rz.PIC_RZ_ALL)
+        o.step(emit=True, collide=True)
+        assert np.array_equal(g.grid("rho"), o.Q)
+        _compare_all(g, o, 1e-9)
+    m = g.moments()
+    print("events", m["events"], "n_cu2", m["n_cu2"], flush=True)
+    assert np.array_equal(m["events"], o.events)
+    assert np.array_equal(m["absorbed"], o.absorbed)
