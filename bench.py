@@ -753,7 +753,7 @@ def rz_cpu_baseline(geo, per_species, steps):
     from paper_2402_08404_amd import workloads as W
     load = W.rz_load(geo, (per_species,) * 3, rng=np.random.default_rng(11))
     o = RZ(geo["nr"], geo["nz"], geo["h"], geo["tip_r"], geo["tip_h"], geo["apex_field"], geo["dt"], geo["m_ion"],
-           seed=geo["seed"], xs=geo["xs"], fn_rings=geo["fn_rings"])
+           seed=geo["seed"], xs=geo["xs"], fn_rings=geo["fn_rings"], cu2=geo["cu2"])
     nid = 0
     for s in range(3):
         o.load(s, load[s], np.arange(nid, nid + per_species))
@@ -783,7 +783,7 @@ def rz_main(args, log):
     caps = [int(1.25 * counts[0]) + 65536, int(1.25 * counts[1]) + 4096, counts[2] + 1]
     keys = ("nr", "nz", "h", "tip_r", "tip_h", "apex_field", "dt", "m_ion")
     sim = rz.RZSimulation(**{k: geo[k] for k in keys}, load=load, caps=caps, step_rtol=1e-8, seed=geo["seed"],
-                          xs=geo["xs"], fn_rings=geo["fn_rings"])
+                          xs=geo["xs"], fn_rings=geo["fn_rings"], cu2=geo["cu2"])
     del load
     log(f"[bench] rz instance ready ({time.perf_counter() - t0:.1f} s), {sum(counts)} particles")
     sim.step(1, rz.PIC_RZ_DEPOSIT | rz.PIC_RZ_SOLVE)
@@ -822,8 +822,8 @@ def rz_main(args, log):
     ach = push_bytes / t_push / 1e9
     cpu = None if args.no_cpu_baseline else rz_cpu_baseline(geo, 2000, 2)
     out = {
-        "metric": "particle-steps/s (axisymmetric variant: emission, push, collisions, field ionization, "
-                  "deposit, CG solve)",
+        "metric": "particle-steps/s (axisymmetric variant: emission, push, collisions with Cu2+, field "
+                  "ionization, deposit, CG solve)",
         "value": float(value), "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
@@ -834,6 +834,7 @@ def rz_main(args, log):
                      "launch_us": t_push * 1e6, "bytes": push_bytes},
         "cpu_baseline": cpu,
         "alive": [n0, n1], "events": m1["events"].tolist(), "injected": int(m1["injected"]),
+        "n_cu2": int(m1["n_cu2"]),
         "cg_iterations_per_step": (iters / args.steps) if args.rz_iters else None,
     }
     sim.close()

@@ -230,10 +230,12 @@ def rz_context(seed: int = 3) -> dict:
     (257 x 1537 nodes: 256 and 1536 cells, which halve down to a few nodes
     for the multigrid preconditioner), 10 GV/m at the apex, dt = 2.5e-16 s
     (an electron at 10^6 m/s moves 0.05 spacings a step), the synthetic
-    tables, 64 emission rings."""
+    tables with the two Cu2+ processes (all four species of the paper), 64
+    emission rings."""
     el, iz, cx = synthetic_tables()
+    iz2, izi = synthetic_tables_cu2()
     return dict(nr=257, nz=1537, h=5e-9, tip_r=50e-9, tip_h=2.5e-6, apex_field=10e9, dt=2.5e-16,
-                m_ion=CU_MASS_U * _AMU, seed=seed, xs=(1e-2, 1e4, el, iz, cx), fn_rings=64)
+                m_ion=CU_MASS_U * _AMU, seed=seed, xs=(1e-2, 1e4, el, iz, cx, iz2, izi), fn_rings=64, cu2=True)
 
 
 def rz_load(geo: dict, counts=(4_000_000, 4_000_000, 4_000_000), r_max: float = 200.0, z_max: float = 1000.0,
