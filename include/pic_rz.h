@@ -5,9 +5,9 @@
  * cathode, the anode and the open side, leapfrog integration).
  *
  * Scope: the node grid with its tip, Poisson's equation in cylindrical
- * finite-volume form solved by FP64 conjugate gradients, the node field,
- * the gather, push, rotation and removal of electrons, Cu+ ions and Cu
- * neutrals, the fixed-point charge deposit, the pair collisions of Table
+ * finite-volume form solved by FP64 conjugate gradients preconditioned by a
+ * geometric multigrid V-cycle, the node field, the gather, push, rotation
+ * and removal of electrons, Cu+ (and Cu2+) ions and Cu neutrals, the fixed-point charge deposit, the pair collisions of Table
  * colls (elastic e-Cu, impact ionization, charge exchange Cu+-Cu, and with
  * cu2 the double ionization of Cu and the ionization of Cu+; Eqs. colp, du,
  * newv), field ionization of Cu (Eq. dfi) and Fowler-Nordheim emission

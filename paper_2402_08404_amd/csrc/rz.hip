@@ -1,9 +1,10 @@
 // rz.hip -- the 2D axisymmetric (r, z) 2D3V variant of the particle-mesh
 // step (Sec. 2.2): node types of the axisymmetric tip, Poisson's equation in
-// cylindrical finite-volume form by FP64 conjugate gradients, the node
-// field, gather + leapfrog push with the rotation back into the r-z plane,
-// removal, the fixed-point deposit, pair collisions over the annular cells
-// (Table colls, Eqs. colp, du, newv), field ionization (Eq. dfi) and
+// cylindrical finite-volume form by FP64 conjugate gradients with a
+// multigrid preconditioner, the node field, gather + leapfrog push with the
+// rotation back into the r-z plane, removal, the fixed-point deposit, pair
+// collisions over the annular cells with Cu2+ as an ion charge state (Table
+// colls, Eqs. colp, du, newv), field ionization (Eq. dfi) and
 // Fowler-Nordheim emission from rings of the tip (Sec. 2.3.1). The
 // discretization and the pairing are stated in pic_rz.h.
 #include <algorithm>
