@@ -33,14 +33,17 @@ METRIC = "particle-steps/s (push+deposit+MCC) + CG iters to 1e-8: learned vs pla
 HBM_PEAK_GBS = 8000.0
 
 
-def workload(name):
+def workload(name, load=None):
+    """Configuration, counts, temperatures and load region of a workload;
+    load overrides the region ("box": uniform over the vacuum box, the
+    default of gpu_scale; "near_tip": clustered in rho <= 3 r, z < H + 2 r)."""
     import numpy as np
     from paper_2402_08404_amd import workloads as W
     if name == "gpu_scale":
         cfg = W.gpu_scale()
         counts = (16_000_000, 1_000_000, 3_000_000)
         kT = (5.0, 1.0, 0.1)
-        region = "box"
+        region = load or "box"
     elif name == "tiny":
         cfg = W.tiny()
         counts = (20000, 200, 2000)
@@ -161,10 +164,10 @@ def measured_traffic(kernel: str):
 def _cpu_worker(arg):
     """One single-threaded oracle process of the CPU baseline: set up its
     sample, wait for the others, then time its steps."""
-    cfg_name, sub, steps, seed, barrier = arg
+    cfg_name, load, sub, steps, seed, barrier = arg
     import oracle
     from paper_2402_08404_amd import workloads as W
-    cfg, counts, kT, region, _ = workload(cfg_name)
+    cfg, counts, kT, region, _ = workload(cfg_name, load)
     o = oracle.Oracle(cfg, laplace=False)
     o.load(W.initial_load(cfg, counts=sub, kT_eV=kT, region=region, seed=seed))
     o.set_phi(W.synthetic_potential(cfg, o.V0))
@@ -179,7 +182,7 @@ def _cpu_worker(arg):
     return n, time.perf_counter() - t0
 
 
-def cpu_baseline(cfg_name, sample, steps, np, procs=0):
+def cpu_baseline(cfg_name, sample, steps, np, procs=0, load=None):
     """The CPU oracle (FP64, single-threaded C) on a bounded sample of the same
     workload, run as `procs` concurrent processes (default: every host core
     up to 16), each on its own sample of `sample` particles with the same
@@ -190,7 +193,7 @@ def cpu_baseline(cfg_name, sample, steps, np, procs=0):
     synthetic potential stands in for the field. Runs before the GPU is
     touched (the processes are forked)."""
     import multiprocessing as mp
-    cfg, counts, kT, region, _ = workload(cfg_name)
+    cfg, counts, kT, region, _ = workload(cfg_name, load)
     ncpu = os.cpu_count() or 1
     procs = procs or min(16, ncpu)
     frac = sample / sum(counts)
@@ -198,7 +201,7 @@ def cpu_baseline(cfg_name, sample, steps, np, procs=0):
     ctx = mp.get_context("fork")
     barrier = ctx.Manager().Barrier(procs)
     with ctx.Pool(procs) as pool:
-        res = pool.map(_cpu_worker, [(cfg_name, sub, steps, cfg.seed + 7 + k, barrier) for k in range(procs)])
+        res = pool.map(_cpu_worker, [(cfg_name, load, sub, steps, cfg.seed + 7 + k, barrier) for k in range(procs)])
     n_tot = sum(n for n, _ in res)
     t_max = max(t for _, t in res)
     model = ""
@@ -223,6 +226,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="gpu_scale", choices=["gpu_scale", "tiny"])
+    ap.add_argument("--load", default=None, choices=["box", "near_tip"],
+                    help="gpu_scale's load: uniform over the box (default) or clustered near the tip")
     ap.add_argument("--solver", default="mgcg", choices=["cg", "mgcg", "mixed"])
     ap.add_argument("--sort-every", type=int, default=0,
                     help="reorder period of the particle arrays (0: the tuned value for this grid, else 16)")
@@ -286,7 +291,8 @@ def main():
     if not (args.no_cpu_baseline or args.calibrate_copy or args.batch or args.unet or args.learned_experiment
             or args.rz):
         print("[bench] cpu baseline (oracle processes)", file=sys.stderr, flush=True)
-        cpu_base = cpu_baseline(args.workload, args.cpu_sample, args.cpu_steps, __import__("numpy"), args.cpu_procs)
+        cpu_base = cpu_baseline(args.workload, args.cpu_sample, args.cpu_steps, __import__("numpy"), args.cpu_procs,
+                                args.load)
     import torch
     if args.calibrate_copy:
         n = args.calibrate_copy * (1 << 20) // 4
@@ -312,7 +318,7 @@ def main():
     if args.unet:
         return unet_main(args, log)
 
-    cfg, counts, kT, region, np = workload(args.workload)
+    cfg, counts, kT, region, np = workload(args.workload, args.load)
     solver = {"cg": pic.PIC_SOLVER_CG, "mgcg": pic.PIC_SOLVER_MGCG, "mixed": pic.PIC_SOLVER_MIXED}[args.solver]
     fp32 = args.workload == "gpu_scale"
     caps = (counts[0] + counts[2] + max(counts[0] // 8, 4096), counts[1] + counts[2] + max(counts[1] // 8, 4096),
@@ -458,7 +464,7 @@ def main():
         "dtype": "f32" if fp32 else "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "grid": [cfg.nx, cfg.ny, cfg.nz], "h_m": cfg.h,
-                   "particles": list(counts), "particle_state": "fp32" if fp32 else "fp64",
+                   "particles": list(counts), "load": region, "particle_state": "fp32" if fp32 else "fp64",
                    "poisson": f"{args.solver} fp64 rtol 1e-8, guess "
                               + ("extrapolated from the two previous steps" if args.step_guess else "previous step"),
                    "sort_every": args.sort_every,

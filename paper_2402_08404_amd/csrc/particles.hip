@@ -789,7 +789,8 @@ __device__ inline void mcc_range(int64_t nc, int64_t nw, int64_t gw, int64_t& cb
 // that can have a collision (all of them when the sorted order is to be
 // written back) in its own segment of the list (the part of the list from
 // the first cell of its range on; no counter shared between wavefronts).
-// Larger cells are listed for k_mcc_big.
+// Larger cells are listed for k_mcc_big: up to kMidCell particles from the
+// start of the list, more from its end.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_mcc_small(MccArgs<T> a) {
     __shared__ double pn[2][kSmallCell + 1];
@@ -813,9 +814,13 @@ __global__ __launch_bounds__(kBlock) void k_mcc_small(MccArgs<T> a) {
                 o0 = a.off[c];
                 n = (int)(a.off[c + 1] - o0);
             }
-            if (n > kSmallCell) {
+            if (n > kSmallCell && n <= kMidCell) {
                 unsigned long long p = atomicAdd(&a.st->n_big, 1ull);
                 a.big[p] = (uint32_t)c;
+            } else if (n > kMidCell) {
+                // the larger cells from the end of the list
+                unsigned long long p = atomicAdd(&a.st->n_big2, 1ull);
+                a.big[a.nc - 1 - (int64_t)p] = (uint32_t)c;
             }
             const bool act = n >= 2 && n <= kSmallCell;
             const unsigned long long m = __ballot(act);
@@ -880,19 +885,23 @@ __global__ __launch_bounds__(kBlock) void k_mcc_cells(MccArgs<T> a) {
 
 // One wavefront per cell with more than kSmallCell particles: bitonic sort of
 // the (species, id) keys in LDS, then projectiles handled across the lanes.
-template <typename T>
+// CAP = kMidCell takes the cells listed from the start of the list (small
+// LDS arrays, so that many wavefronts share a compute unit), CAP = kBigCell
+// those from its end up to kBigCell particles.
+template <typename T, int CAP>
 __global__ __launch_bounds__(64) void k_mcc_big(MccArgs<T> a) {
-    __shared__ uint64_t kk[kBigCell];
-    __shared__ uint32_t ee[kBigCell];
-    __shared__ uint8_t used[kBigCell];
+    __shared__ uint64_t kk[CAP];
+    __shared__ uint32_t ee[CAP];
+    __shared__ uint8_t used[CAP];
+    constexpr bool kBack = CAP > kMidCell;
     int cnt[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int lane = threadIdx.x;
-    const int64_t nbig = (int64_t)a.st->n_big;
+    const int64_t nbig = (int64_t)(kBack ? a.st->n_big2 : a.st->n_big);
     for (int64_t b = blockIdx.x; b < nbig; b += gridDim.x) {
-        uint32_t c = a.big[b];
+        uint32_t c = kBack ? a.big[a.nc - 1 - b] : a.big[b];
         uint32_t o0 = a.off[c];
         int n = (int)(a.off[c + 1] - o0);
-        if (n > kBigCell) continue;  // k_mcc_huge
+        if (n > CAP) continue;  // k_mcc_huge
         int P = 1;
         while (P < n) P <<= 1;
         for (int t = lane; t < P; t += 64) {
@@ -1004,9 +1013,9 @@ __global__ __launch_bounds__(kHugeThreads) void k_mcc_huge(MccArgs<T> a, uint32_
     __shared__ int sh[kHugeThreads / 64];
     int cnt[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
     const int tid = threadIdx.x;
-    const int64_t nbig = (int64_t)a.st->n_big;
+    const int64_t nbig = (int64_t)a.st->n_big2;  // the larger cells, listed from the end
     for (int64_t b = blockIdx.x; b < nbig; b += gridDim.x) {
-        const uint32_t c = a.big[b];
+        const uint32_t c = a.big[a.nc - 1 - b];
         const uint32_t o0 = a.off[c];
         const int n = (int)(a.off[c + 1] - o0);
         if (n <= kBigCell) continue;
@@ -1415,6 +1424,7 @@ __global__ void k_step_reset(DevState* st) {
     st->n_prod_kind[0] = st->n_prod_kind[1] = 0;
     st->n_ev = 0;
     st->n_big = 0;
+    st->n_big2 = 0;
     for (int s = 0; s < 3; ++s) {
         st->smax_bits[s] = 0;
         st->n_push[s] = st->n_slots[s];
@@ -1569,7 +1579,8 @@ struct PairArgs {
     Grid g;
     const uint32_t* off;
     const uint2* bins;
-    const uint32_t* big;     // cells of more than kSmallCell particles (count st->n_big)
+    const uint32_t* big;     // cells of more than kSmallCell particles: up to kMidCell from the start
+                             // (count st->n_big), more from the end (count st->n_big2)
     const uint32_t* nflag;   // neutral slot: step + 1 if it had an event this step
     DevState* st;
     uint32_t step;
@@ -1819,16 +1830,19 @@ __global__ __launch_bounds__(kBlock) void k_pair_small(PairArgs<T> a) {
     }
 }
 
-// one wavefront (block of 64) per listed big cell
-template <typename T>
+// one wavefront (block of 64) per listed big cell: CAP = kMidCell for the
+// cells listed from the start of the list, CAP = kBigCell for those from its
+// end
+template <typename T, int CAP>
 __global__ __launch_bounds__(64) void k_pair_big(PairArgs<T> a) {
-    __shared__ uint64_t kk[kBigCell];
-    __shared__ uint32_t ee[kBigCell];
+    __shared__ uint64_t kk[CAP];
+    __shared__ uint32_t ee[CAP];
+    constexpr bool kBack = CAP > kMidCell;
     const int lane = threadIdx.x;
     int cnt[3] = {0, 0, 0};
-    const int64_t nbig = (int64_t)a.st->n_big;
+    const int64_t nbig = (int64_t)(kBack ? a.st->n_big2 : a.st->n_big);
     for (int64_t b = blockIdx.x; b < nbig; b += gridDim.x) {
-        const uint32_t c = a.big[b];
+        const uint32_t c = kBack ? a.big[a.nc - 1 - b] : a.big[b];
         const uint32_t o0 = a.off[c];
         const int n = (int)(a.off[c + 1] - o0);
         if (n > kBigCell) {  // not supported by the pairing of this kernel
@@ -2124,7 +2138,8 @@ static hipError_t collide_t(pic_ctx* c, bool record) {
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_mcc_compact<T>, dim3(gm), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(k_mcc_cells<T>, dim3(side ? 256 : 2048), dim3(kBlock), 0, c->stream, a);
-    hipLaunchKernelGGL(k_mcc_big<T>, dim3(1024), dim3(64), 0, c->stream, a);
+    hipLaunchKernelGGL((k_mcc_big<T, kMidCell>), dim3(8192), dim3(64), 0, c->stream, a);
+    hipLaunchKernelGGL((k_mcc_big<T, kBigCell>), dim3(1024), dim3(64), 0, c->stream, a);
     hipLaunchKernelGGL(k_mcc_huge<T>, dim3(64), dim3(kHugeThreads), 0, c->stream, a, c->rank_flag);
     toc(c, tm);
     hipLaunchKernelGGL(k_fi_resolve<T>, dim3(grid_for(c->buf.cap[2])), dim3(kBlock), 0, c->stream, a, c->fi_list,
@@ -2204,7 +2219,8 @@ static hipError_t collide_t(pic_ctx* c, bool record) {
         pa.rec_pf = c->rec_pf;
         hipLaunchKernelGGL(k_pair_small<T>, dim3(side ? std::min(grid_for(g.nkeys), 1024u) : grid_for(g.nkeys)),
                            dim3(kBlock), 0, c->stream, pa);
-        hipLaunchKernelGGL(k_pair_big<T>, dim3(256), dim3(64), 0, c->stream, pa);
+        hipLaunchKernelGGL((k_pair_big<T, kMidCell>), dim3(8192), dim3(64), 0, c->stream, pa);
+        hipLaunchKernelGGL((k_pair_big<T, kBigCell>), dim3(256), dim3(64), 0, c->stream, pa);
         if (pa.rec) {
             uint32_t* wrec = c->dyn + 16;
             hipLaunchKernelGGL(k_words_rec, dim3(1), dim3(1), 0, c->stream, c->st, wrec, c->bm_words);

@@ -25,6 +25,7 @@ constexpr double kPi = 3.14159265358979323846;
 
 constexpr uint32_t kDead = 0xFFFFFFFFu;      // id of a free slot, key of a removed particle
 constexpr int kSmallCell = 16;                // cells up to this many particles: one thread each
+constexpr int kMidCell = 256;                 // listed cells up to this many: a small-LDS wavefront each
 constexpr int kBigCell = 4096;                // cells up to this many: one wavefront each
 constexpr int kBlock = 256;
 
@@ -82,6 +83,7 @@ struct DevState {
     unsigned long long coulomb_pairs;  // cumulative Coulomb scatterings
     unsigned long long n_rec;          // recombinations of this collide phase
     unsigned long long recombinations; // cumulative recombinations
+    unsigned long long n_big2;         // listed cells of more than kMidCell particles (from the list's end)
 };
 
 // Cells are numbered tile-major: tiles of kTile^3 cells, tile index
