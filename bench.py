@@ -103,11 +103,12 @@ def pmc_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib, 
         for r in csv.DictReader(open(path)):
             name = r["Kernel_Name"].split("(")[0].replace("void ", "").strip()
             d.setdefault((name, int(r["Grid_Size"])), []).append(float(r["Counter_Value"]))
-        best = {}
+        best, grids = {}, {}
         for (name, grid), v in d.items():
+            grids.setdefault(name, {})[grid] = statistics.median(v)
             if name not in best or grid > best[name][0]:
                 best[name] = (grid, statistics.median(v), len(v))
-        return best
+        return best, grids
 
     def copy_kib(path):
         v = [float(r["Counter_Value"]) for r in csv.DictReader(open(path)) if "copyBuffer" in r["Kernel_Name"]
@@ -116,12 +117,15 @@ def pmc_summary(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_mib, 
 
     f_fetch = copy_mib * 1024.0 / copy_kib(copy_fetch_csv)
     f_write = copy_mib * 1024.0 / copy_kib(copy_write_csv)
-    fe, wr = per_kernel(fetch_csv), per_kernel(write_csv)
+    (fe, fe_g), (wr, wr_g) = per_kernel(fetch_csv), per_kernel(write_csv)
     out = {"fetch_scale": f_fetch, "write_scale": f_write, "copy_mib": copy_mib, "kernels": {}}
     for name in sorted(set(fe) & set(wr)):
+        by_grid = {str(gr): 1024.0 * (fe_g[name][gr] * f_fetch + wr_g[name][gr] * f_write)
+                   for gr in sorted(set(fe_g[name]) & set(wr_g[name]))}
         out["kernels"][name] = {"grid": fe[name][0], "fetch_kib": fe[name][1], "write_kib": wr[name][1],
                                 "dispatches": fe[name][2],
-                                "bytes": 1024.0 * (fe[name][1] * f_fetch + wr[name][1] * f_write)}
+                                "bytes": 1024.0 * (fe[name][1] * f_fetch + wr[name][1] * f_write),
+                                "bytes_by_grid": by_grid}
     with open(out_path, "w") as f:
         json.dump(out, f, indent=1, sort_keys=True)
     return out
@@ -265,6 +269,7 @@ def main():
                     help="the axisymmetric variant on the paper's geometry: every stage of its step")
     ap.add_argument("--rz-scale", type=float, default=1.0, help="scale factor of the axisymmetric particle counts")
     ap.add_argument("--rz-iters", action="store_true", help="with --rz: read the CG iterations after every step")
+    ap.add_argument("--pmc-out", default=TRAFFIC_FILE, help="where --pmc-summary writes its JSON")
     ap.add_argument("--pmc-summary", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV",
                                                         "COPY_MIB"),
                     help="write the HBM traffic summary of rocprofv3 --pmc runs to profiles/ and exit")
@@ -281,7 +286,7 @@ def main():
 
     if args.pmc_summary:
         a = args.pmc_summary
-        out = pmc_summary(a[0], a[1], a[2], a[3], float(a[4]), TRAFFIC_FILE)
+        out = pmc_summary(a[0], a[1], a[2], a[3], float(a[4]), args.pmc_out)
         print(json.dumps({k: round(v["bytes"] / 1e6, 1) for k, v in out["kernels"].items()}, indent=1))
         return
     if args.trace_summary:
@@ -775,6 +780,9 @@ def rz_cpu_baseline(geo, per_species, steps):
                       f"({wall:.1f} s, one thread; the direct solve of the grid dominates)"}
 
 
+kBlockRz = 256  # threads per block of the axisymmetric particle kernels (grid = capacity rounded up)
+
+
 def rz_main(args, log):
     """The axisymmetric variant on the paper's geometry: emission, push,
     collisions, field ionization, deposit and the CG solve in every step."""
@@ -826,6 +834,16 @@ def rz_main(args, log):
     t_push = ev[0].elapsed_time(ev[1]) * 1e-3 / reps
     push_bytes = 84.0 * alive + 16.0 * nn
     ach = push_bytes / t_push / 1e9
+    # HBM bytes of one pass (the three species' launches) from the counters
+    # in profiles/traffic_rz_context.json, where they were taken
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "traffic_rz_context.json")
+    if os.path.exists(tf):
+        with open(tf) as f:
+            kp = json.load(f)["kernels"].get("pic_rz::k_push")
+        grids = [str(kBlockRz * ((c + kBlockRz - 1) // kBlockRz)) for c in caps]
+        if kp and all(g in kp["bytes_by_grid"] for g in grids):
+            traffic = sum(kp["bytes_by_grid"][g] for g in grids)
     cpu = None if args.no_cpu_baseline else rz_cpu_baseline(geo, 2000, 2)
     out = {
         "metric": "particle-steps/s (axisymmetric variant: emission, push, collisions with Cu2+, field "
@@ -836,7 +854,7 @@ def rz_main(args, log):
         "config": {"workload": "rz_context", "grid": [geo["nr"], geo["nz"]], "h_nm": geo["h"] * 1e9,
                    "tip_r_nm": geo["tip_r"] * 1e9, "tip_h_um": geo["tip_h"] * 1e6, "particles": list(counts)},
         "roofline": {"bound": "hbm", "kernel": "k_push (all species, one pass)", "achieved": ach, "peak": 8000.0,
-                     "unit": "GB/s", "frac": ach / 8000.0, "traffic": None,
+                     "unit": "GB/s", "frac": ach / 8000.0, "traffic": traffic,
                      "launch_us": t_push * 1e6, "bytes": push_bytes},
         "cpu_baseline": cpu,
         "alive": [n0, n1], "events": m1["events"].tolist(), "injected": int(m1["injected"]),
