@@ -65,9 +65,8 @@
  * plus one with probability frac(N) (draw (patch, step, 6, 0)); electron j
  * at ring parameter U from draw (patch, step, 6, 1 + j), 10^-3 spacings out,
  * at rest; ids continue from next_id in patch order. New particles are
- * appended at the end of the species' slots, so within each species the
- * slot order is the id order (which the pairing relies on): the initial ids
- * of each species must increase strictly with the slot.
+ * appended at the end of the species' slots. Ids must be unique and not
+ * 0xFFFFFFFF; the pairing and the products follow the ids, not the slots.
  */
 #ifndef PIC_RZ_H
 #define PIC_RZ_H
@@ -90,7 +89,9 @@ typedef struct pic_rz_config {
     double m_ion;          /* Cu mass [kg] */
     double laplace_rtol;   /* tolerance of the unit-anode solve at init */
     int32_t maxit;         /* iteration limit of the solve inside pic_rz_step */
-    int32_t reserved;
+    int32_t sort_every;    /* with collisions: every this many steps (0: never) the particles of
+                              each species are reordered by cell, ascending id within a cell,
+                              freed slots dropped (slots change, ids stay) */
     double step_rtol;      /* tolerance of the solve inside pic_rz_step */
     /* collisions, field ionization, emission */
     uint64_t seed;         /* Philox key of every draw */
@@ -170,8 +171,8 @@ pic_status pic_rz_scratch_size(const pic_rz_config* cfg, const int64_t cap[3], s
  * unit-anode solve (to laplace_rtol) into phi1, V0, phi = V0 phi1 and its
  * field; next_id = one above the largest initial id (0 without particles).
  * Buffers are caller-owned; the context keeps their pointers.
- * Errors: PIC_E_INVALID_ARG (config, buffers, n > cap, initial ids of a
- * species not strictly increasing with the slot or free), PIC_E_NOT_CONVERGED,
+ * Errors: PIC_E_INVALID_ARG (config, buffers, n > cap, an initial id
+ * 0xFFFFFFFF, a charge state other than 1 or 2), PIC_E_NOT_CONVERGED,
  * PIC_E_HIP. */
 pic_status pic_rz_init(const pic_rz_config* cfg, const pic_rz_buffers* bufs, void* hip_stream, pic_rz_ctx** out);
 

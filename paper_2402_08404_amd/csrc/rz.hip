@@ -50,6 +50,7 @@ struct State {
     int skip;                      // the stage's new particles did not fit
     unsigned int nbig;             // (species, cell) keys above kRankSmall particles
     unsigned long long ngrp[3];    // slots in use when the particles were grouped by cell
+    unsigned long long nprod;      // entries of the product list of the collide stage
 };
 
 struct Geo {
@@ -631,14 +632,13 @@ __global__ void k_qsum(const int64_t* rho, int64_t nn, unsigned long long* out) 
 }
 
 // ---------------------------------------------------------------------------
-// Initial ids: strictly increasing with the slot within a species (and none
-// free); next_id one above the largest.
+// Initial ids: none free; next_id one above the largest.
 __global__ void k_check_ids(const uint32_t* id, int64_t n, State* st) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const uint32_t v = id[p];
-    if (v == kDead || (p + 1 < n && v >= id[p + 1])) atomicOr(&st->skip, 1);
-    if (p + 1 == n) atomicMax(&st->next_id, (unsigned long long)v + 1ull);
+    if (v == kDead) atomicOr(&st->skip, 1);
+    else atomicMax(&st->next_id, (unsigned long long)v + 1ull);
 }
 
 // Initial ion charge states: 1 or 2.
@@ -747,6 +747,7 @@ __global__ void k_zero_u32(uint32_t* x, int64_t n, State* st) {
     if (i < n) x[i] = 0u;
     if (i == 0) {
         st->nbig = 0;
+        st->nprod = 0;
         for (int s = 0; s < 3; ++s) st->ngrp[s] = st->n[s];
     }
 }
@@ -764,7 +765,8 @@ struct CollArgs {
     uint32_t* crank;   // every slot's rank (id order) in its cell
     uint32_t* start;   // 3 nc exclusive prefix of cnt
     uint32_t* seg;     // slots grouped by (species, cell), unordered within a cell
-    uint32_t* sorted;  // the same, ascending slot (= id) order within a cell
+    uint32_t* segid;   // their ids
+    uint32_t* sorted;  // the same, ascending id order within a cell
     uint32_t* big;     // keys of the cells above kRankSmall particles
     int32_t* cellof;   // cell of every slot (-1 free)
     uint8_t* used;     // the slot's particle had an event this step
@@ -773,8 +775,11 @@ struct CollArgs {
     uint8_t* iflag;    // ion slot: 1 ionized to Cu2+ this step
     double* vei;       // ion slot: the new electron's velocity of that ionization
     uint8_t* charge;   // ion charge states (Cu2+ only)
-    uint32_t *pci, *pce;  // per product entry (impact, field, ion ionization): new ions, new electrons
-    uint32_t *ppi, *ppe;  // their exclusive prefixes
+    unsigned long long* pkey;  // product list: kind << 32 | id (kind 0 impact, 1 field, 2 Cu+ ionization)
+    uint32_t* pslot;           // the neutral's (kinds 0, 1) or the ion's (kind 2) slot
+    uint32_t *pci, *pce;       // per sorted entry: new ions, new electrons (0 beyond the list)
+    uint32_t *ppi, *ppe;       // their exclusive prefixes
+    int64_t pcap;              // cap[1] + cap[2], the longest list
     const double* E;
     const double* xs;
     int xs_n;
@@ -814,7 +819,9 @@ __global__ __launch_bounds__(kBlock) void k_place(CollArgs a, int s) {
     if (p >= (int64_t)a.st->n[s]) return;
     const int32_t c = a.cellof[a.off[s] + p];
     if (c < 0) return;
-    a.seg[a.start[s * a.nc + c] + a.cpos[a.off[s] + p]] = (uint32_t)p;
+    const int64_t j = a.start[s * a.nc + c] + a.cpos[a.off[s] + p];
+    a.seg[j] = (uint32_t)p;
+    a.segid[j] = a.id[s][p];
 }
 
 // The deposit of the grouped electrons and ions in grouped order: the lanes
@@ -863,15 +870,15 @@ __global__ __launch_bounds__(kBlock) void k_deposit_grouped(CollArgs a, int64_t*
     atomicAdd(q + n0 + a.g.nr + 1, (unsigned long long)w[3]);
 }
 
-// Cells of up to kRankSmall particles of a species: each grouped slot's
-// rank among its cell's slots (the number of smaller ones) is its place in
-// ascending order; the lanes of a wavefront that share a cell read the same
-// addresses together. Larger cells are listed for k_sort_big.
+// Cells of up to kRankSmall particles of a species: each grouped particle's
+// rank among its cell's particles (the number of smaller ids) is its place
+// in ascending id order; the lanes of a wavefront that share a cell read the
+// same addresses together. Larger cells are listed for k_sort_big.
 __global__ __launch_bounds__(kBlock) void k_rank(CollArgs a) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= (int64_t)a.st->total) return;  // the particles grouped, from the scan of the counts
     const int s = j < (int64_t)a.start[a.nc] ? 0 : (j < (int64_t)a.start[2 * a.nc] ? 1 : 2);
-    const uint32_t p = a.seg[j];
+    const uint32_t p = a.seg[j], myid = a.segid[j];
     const int64_t key = s * a.nc + a.cellof[a.off[s] + p];
     const int64_t b = a.start[key], m = a.cnt[key];
     if (m > kRankSmall) {
@@ -879,17 +886,17 @@ __global__ __launch_bounds__(kBlock) void k_rank(CollArgs a) {
         return;
     }
     int64_t rank = 0;
-    for (int64_t k = 0; k < m; ++k) rank += a.seg[b + k] < p ? 1 : 0;
+    for (int64_t k = 0; k < m; ++k) rank += a.segid[b + k] < myid ? 1 : 0;
     a.sorted[b + rank] = p;
     a.crank[a.off[s] + p] = (uint32_t)rank;
 }
 
 // The listed cells, one per block in turn: up to kRankLds particles by a
-// bitonic sort in LDS (padded to a power of two with 0xFFFFFFFF, above every
-// slot), beyond that by rank counting over LDS tiles of the cell (quadratic
-// in the cell's particles).
+// bitonic sort in LDS of id << 32 | slot (padded to a power of two with keys
+// above every entry), beyond that by rank counting of the ids over LDS tiles
+// of the cell (quadratic in the cell's particles).
 __global__ __launch_bounds__(kBlock) void k_sort_big(CollArgs a) {
-    __shared__ uint32_t keys[kRankLds];
+    __shared__ unsigned long long keys[kRankLds];
     const uint32_t nbig = a.st->nbig;
     for (uint32_t e = blockIdx.x; e < nbig; e += gridDim.x) {
         const int64_t key = a.big[e];
@@ -897,14 +904,15 @@ __global__ __launch_bounds__(kBlock) void k_sort_big(CollArgs a) {
         if (m <= kRankLds) {
             int P = 1;
             while (P < m) P <<= 1;
-            for (int i = threadIdx.x; i < P; i += blockDim.x) keys[i] = i < m ? a.seg[b + i] : 0xFFFFFFFFu;
+            for (int i = threadIdx.x; i < P; i += blockDim.x)
+                keys[i] = i < m ? ((unsigned long long)a.segid[b + i] << 32 | a.seg[b + i]) : ~0ull;
             __syncthreads();
             for (int k = 2; k <= P; k <<= 1) {
                 for (int jj = k >> 1; jj > 0; jj >>= 1) {
                     for (int i = threadIdx.x; i < P; i += blockDim.x) {
                         const int ixj = i ^ jj;
                         if (ixj > i) {
-                            const uint32_t x = keys[i], y = keys[ixj];
+                            const unsigned long long x = keys[i], y = keys[ixj];
                             if ((x > y) == ((i & k) == 0)) {
                                 keys[i] = y;
                                 keys[ixj] = x;
@@ -916,20 +924,22 @@ __global__ __launch_bounds__(kBlock) void k_sort_big(CollArgs a) {
             }
             const int sp = (int)(key / a.nc);
             for (int i = threadIdx.x; i < m; i += blockDim.x) {
-                a.sorted[b + i] = keys[i];
-                a.crank[a.off[sp] + keys[i]] = (uint32_t)i;
+                const uint32_t slot = (uint32_t)(keys[i] & 0xFFFFFFFFull);
+                a.sorted[b + i] = slot;
+                a.crank[a.off[sp] + slot] = (uint32_t)i;
             }
             __syncthreads();  // keys are reused by the next cell
         } else {
             for (int64_t i0 = 0; i0 < m; i0 += blockDim.x) {
                 const int64_t i = i0 + threadIdx.x;
                 const uint32_t p = i < m ? a.seg[b + i] : 0xFFFFFFFFu;
+                const unsigned long long myid = i < m ? a.segid[b + i] : ~0ull;
                 int64_t rank = 0;
                 for (int64_t t0 = 0; t0 < m; t0 += kRankLds) {
                     const int64_t tn = m - t0 < kRankLds ? m - t0 : kRankLds;
-                    for (int64_t k = threadIdx.x; k < tn; k += blockDim.x) keys[k] = a.seg[b + t0 + k];
+                    for (int64_t k = threadIdx.x; k < tn; k += blockDim.x) keys[k] = a.segid[b + t0 + k];
                     __syncthreads();
-                    for (int64_t k = 0; k < tn; ++k) rank += keys[k] < p ? 1 : 0;
+                    for (int64_t k = 0; k < tn; ++k) rank += keys[k] < myid ? 1 : 0;
                     __syncthreads();
                 }
                 if (i < m) {
@@ -1140,41 +1150,126 @@ __global__ __launch_bounds__(kBlock) void k_fi(CollArgs a) {
     }
 }
 
-// Products in the order impact ionizations (entries 0 .. cap2 - 1, by
-// neutral slot), field ionizations (cap2 .. 2 cap2 - 1), ionizations of
-// Cu+ (2 cap2 .. 2 cap2 + cap1 - 1, by ion slot): the new ions and electrons
-// of every entry, whose exclusive prefixes give each product its slots and
-// ids (ids are taken in product order, the ion's first).
-__global__ __launch_bounds__(kBlock) void k_prod_counts(CollArgs a, int64_t L) {
+// Products: impact ionizations (kind 0), field ionizations (kind 1), each by
+// ascending neutral id, then ionizations of Cu+ (kind 2) by ascending ion
+// id. The product entries are appended to a list (key kind << 32 | id, and
+// the slot), the list is sorted by key, and exclusive prefixes of the new
+// ions and electrons of the sorted entries give each product its slots and
+// ids (ids in product order, the ion's first).
+__global__ __launch_bounds__(kBlock) void k_prod_list(CollArgs a) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= L) return;
     const int64_t c2 = a.cap[2];
-    uint32_t ni = 0, ne = 0;
-    if (e < 2 * c2) {
-        const int64_t p = e < c2 ? e : e - c2;
-        if (p < (int64_t)a.st->n[2]) {
-            const uint8_t f = a.pflag[p];
-            if (e < c2 && (f == 1 || f == 3)) {
-                ni = 1;
-                ne = f == 3 ? 2 : 1;
-            } else if (e >= c2 && f == 2) {
-                ni = 1;
-                ne = 1;
+    bool put = false;
+    unsigned long long key = 0;
+    uint32_t slot = 0;
+    if (e < c2) {
+        if (e < (int64_t)a.st->n[2]) {
+            const uint8_t f = a.pflag[e];
+            if (f) {
+                put = true;
+                key = ((unsigned long long)(f == 2 ? 1 : 0) << 32) | a.id[2][e];
+                slot = (uint32_t)e;
             }
         }
-    } else {
-        const int64_t p = e - 2 * c2;
-        if (p < (int64_t)a.st->n[1] && a.iflag[p]) ne = 1;
+    } else if (e < c2 + a.cap[1]) {
+        const int64_t p = e - c2;
+        if (p < (int64_t)a.st->n[1] && a.iflag[p]) {
+            put = true;
+            key = (2ull << 32) | a.id[1][p];
+            slot = (uint32_t)p;
+        }
     }
-    a.pci[e] = ni;
-    a.pce[e] = ne;
+    const unsigned long long q = pic::wave_append(&a.st->nprod, put);
+    if (put) {
+        a.pkey[q] = key;
+        a.pslot[q] = slot;
+    }
+}
+
+__device__ inline void pcmpx(unsigned long long* k, uint32_t* v, int64_t n, int64_t i, int64_t j) {
+    if (j >= n) return;  // k[j] is +inf
+    const unsigned long long x = k[i], y = k[j];
+    if (x > y) {
+        k[i] = y;
+        k[j] = x;
+        const uint32_t t = v[i];
+        v[i] = v[j];
+        v[j] = t;
+    }
+}
+
+// Ascending sort of n keys with their values by one block: a bitonic network
+// whose comparators all put the smaller key first (each merge starts with
+// the mirrored pairs), so virtual +inf keys pad n to a power of two without
+// being stored or moved.
+__device__ inline void block_sort(unsigned long long* k, uint32_t* v, int64_t n) {
+    int64_t P = 1;
+    while (P < n) P <<= 1;
+    for (int64_t kk = 2; kk <= P; kk <<= 1) {
+        const int64_t hk = kk >> 1;
+        for (int64_t t = threadIdx.x; t < P / 2; t += blockDim.x) {
+            const int64_t base = (t / hk) * kk, r = t % hk;
+            pcmpx(k, v, n, base + r, base + kk - 1 - r);
+        }
+        __syncthreads();
+        for (int64_t j = hk >> 1; j > 0; j >>= 1) {
+            for (int64_t t = threadIdx.x; t < P / 2; t += blockDim.x) {
+                const int64_t i = (t / j) * 2 * j + t % j;
+                pcmpx(k, v, n, i, i + j);
+            }
+            __syncthreads();
+        }
+    }
+}
+
+constexpr int kProdLds = 4096;  // product lists up to this long are sorted in LDS
+
+__global__ __launch_bounds__(1024) void k_prod_sort(CollArgs a) {
+    __shared__ unsigned long long lk[kProdLds];
+    __shared__ uint32_t lv[kProdLds];
+    const int64_t n = (int64_t)a.st->nprod;
+    if (n <= 1) return;
+    if (n <= kProdLds) {
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            lk[i] = a.pkey[i];
+            lv[i] = a.pslot[i];
+        }
+        __syncthreads();
+        block_sort(lk, lv, n);
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            a.pkey[i] = lk[i];
+            a.pslot[i] = lv[i];
+        }
+    } else {
+        block_sort(a.pkey, a.pslot, n);  // in global memory, the block's own
+    }
+}
+
+// new ions and electrons of every sorted entry, 0 beyond the list
+__global__ __launch_bounds__(kBlock) void k_prod_counts(CollArgs a) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.pcap) return;
+    uint32_t ni = 0, ne = 0;
+    if (j < (int64_t)a.st->nprod) {
+        const uint32_t kind = (uint32_t)(a.pkey[j] >> 32);
+        ne = 1;
+        if (kind == 0) {
+            ni = 1;
+            ne = a.pflag[a.pslot[j]] == 3 ? 2 : 1;
+        } else if (kind == 1) {
+            ni = 1;
+        }
+    }
+    a.pci[j] = ni;
+    a.pce[j] = ne;
 }
 
 // room for the products' ions and electrons and their ids
-__global__ void k_prod_commit(CollArgs a, int64_t L) {
+__global__ void k_prod_commit(CollArgs a) {
     if (threadIdx.x != 0) return;
     State* st = a.st;
     st->skip = 0;
+    const int64_t L = a.pcap;
     const unsigned long long TI = L ? (unsigned long long)a.ppi[L - 1] + a.pci[L - 1] : 0ull;
     const unsigned long long TE = L ? (unsigned long long)a.ppe[L - 1] + a.pce[L - 1] : 0ull;
     if (TI + TE == 0) return;
@@ -1196,18 +1291,17 @@ __global__ void k_prod_commit(CollArgs a, int64_t L) {
     st->next_id += TI + TE;
 }
 
-__global__ __launch_bounds__(kBlock) void k_prod_place(CollArgs a, int64_t L) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= L || a.st->skip) return;
-    const uint32_t ni = a.pci[e], ne = a.pce[e];
-    if (ni + ne == 0) return;
-    const uint64_t oi = a.ppi[e], oe = a.ppe[e];
+__global__ __launch_bounds__(kBlock) void k_prod_place(CollArgs a) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= (int64_t)a.st->nprod || a.st->skip) return;
+    const uint32_t kind = (uint32_t)(a.pkey[j] >> 32);
+    const int64_t p = a.pslot[j];
+    const uint32_t ne = a.pce[j];
+    const uint64_t oi = a.ppi[j], oe = a.ppe[j];
     const uint64_t id0 = a.st->base_id + oi + oe;
     const uint64_t se = a.st->base_n[0] + oe;
-    const int64_t c2 = a.cap[2];
-    if (e >= 2 * c2) {
+    if (kind == 2) {
         // ionization of Cu+: one electron at the ion
-        const int64_t p = e - 2 * c2;
         a.r[0][se] = a.r[1][p];
         a.z[0][se] = a.z[1][p];
         a.vr[0][se] = a.vei[3 * p];
@@ -1216,7 +1310,6 @@ __global__ __launch_bounds__(kBlock) void k_prod_place(CollArgs a, int64_t L) {
         a.id[0][se] = (uint32_t)id0;
         return;
     }
-    const int64_t p = e < c2 ? e : e - c2;
     const uint8_t f = a.pflag[p];
     const uint64_t si = a.st->base_n[1] + oi;
     a.r[1][si] = a.r[2][p];
@@ -1241,6 +1334,54 @@ __global__ __launch_bounds__(kBlock) void k_prod_place(CollArgs a, int64_t L) {
         a.id[0][se + q] = (uint32_t)(id0 + 1 + q);
     }
     a.id[2][p] = kDead;
+}
+
+// Reorder of species s by cell, ascending id in a cell (the grouping's
+// order), freed slots dropped: into the work copies, then back.
+struct ReorderArgs {
+    double *r, *z, *vr, *vt, *vz;
+    uint32_t* id;
+    uint8_t* charge;
+    double *tr, *tz, *tvr, *tvt, *tvz;
+    uint32_t* tid;
+    uint8_t* tcharge;
+    const uint32_t* sorted;
+    const uint32_t* start;  // of the species' first cell; the next species' start, or total
+    int64_t first, next;    // indices into start (next < 0: the grouped total)
+    State* st;
+};
+
+__device__ inline int64_t reorder_count(const ReorderArgs& a) {
+    const int64_t b = a.start[a.first];
+    const int64_t e = a.next >= 0 ? (int64_t)a.start[a.next] : (int64_t)a.st->total;
+    return e - b;
+}
+
+__global__ __launch_bounds__(kBlock) void k_reorder_gather(ReorderArgs a) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= reorder_count(a)) return;
+    const uint32_t p = a.sorted[a.start[a.first] + j];
+    a.tr[j] = a.r[p];
+    a.tz[j] = a.z[p];
+    a.tvr[j] = a.vr[p];
+    a.tvt[j] = a.vt[p];
+    a.tvz[j] = a.vz[p];
+    a.tid[j] = a.id[p];
+    if (a.charge) a.tcharge[j] = a.charge[p];
+}
+
+__global__ __launch_bounds__(kBlock) void k_reorder_back(ReorderArgs a, int sp) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = reorder_count(a);
+    if (j == 0) a.st->n[sp] = (unsigned long long)n;
+    if (j >= n) return;
+    a.r[j] = a.tr[j];
+    a.z[j] = a.tz[j];
+    a.vr[j] = a.tvr[j];
+    a.vt[j] = a.tvt[j];
+    a.vz[j] = a.tvz[j];
+    a.id[j] = a.tid[j];
+    if (a.charge) a.charge[j] = a.tcharge[j];
 }
 
 // room for the T = st->total emitted electrons and their ids
@@ -1404,7 +1545,7 @@ struct Work {
     uint32_t *ccnt = nullptr, *start = nullptr;                          // 3 nc each
     uint32_t *cpos = nullptr, *crank = nullptr;                          // sum of caps each
     uint32_t *ssum = nullptr, *spre = nullptr;                           // chunk sums of the scans
-    uint32_t *seg = nullptr, *sorted = nullptr;                          // sum of caps each
+    uint32_t *seg = nullptr, *segid = nullptr, *sorted = nullptr;        // sum of caps each
     uint32_t* big = nullptr;                                             // 3 nc
     int32_t* cellof = nullptr;
     uint8_t* used = nullptr;
@@ -1412,7 +1553,13 @@ struct Work {
     double* ve = nullptr;      // 6 cap[2]
     uint8_t* iflag = nullptr;  // cap[1]
     double* vei = nullptr;     // 3 cap[1]
-    uint32_t *pci = nullptr, *pce = nullptr, *ppi = nullptr, *ppe = nullptr;  // 2 cap[2] + cap[1] each
+    unsigned long long* pkey = nullptr;         // cap[1] + cap[2]
+    uint32_t* pslot = nullptr;
+    uint32_t *pci = nullptr, *pce = nullptr, *ppi = nullptr, *ppe = nullptr;  // cap[1] + cap[2] each
+    // reorder work copies of one species (the largest capacity)
+    double *tr = nullptr, *tz = nullptr, *tvr = nullptr, *tvt = nullptr, *tvz = nullptr;
+    uint32_t* tid = nullptr;
+    uint8_t* tcharge = nullptr;
     uint32_t* pcnt = nullptr;                   // patches
     uint64_t* poff = nullptr;
     double* z = nullptr;                        // preconditioned residual (nodes)
@@ -1426,7 +1573,8 @@ size_t layout(const pic_rz_config* c, const int64_t cap[3], char* base, Work* w)
     const size_t nn = (size_t)c->nr * c->nz;
     const size_t nc = (size_t)(c->nr - 1) * (c->nz - 1);
     const size_t ncap = (size_t)(cap[0] + cap[1] + cap[2]);
-    const size_t nprod = (size_t)(2 * cap[2] + cap[1]);
+    const size_t nprod = (size_t)(cap[2] + cap[1]);
+    const size_t capmax = (size_t)std::max(cap[0], std::max(cap[1], cap[2]));
     const size_t np = (size_t)patches(c);
     size_t off = 0;
     auto take = [&](size_t b) -> char* {
@@ -1449,6 +1597,7 @@ size_t layout(const pic_rz_config* c, const int64_t cap[3], char* base, Work* w)
     t.ssum = (uint32_t*)take(nscan * 4);
     t.spre = (uint32_t*)take(nscan * 4);
     t.seg = (uint32_t*)take(ncap * 4);
+    t.segid = (uint32_t*)take(ncap * 4);
     t.sorted = (uint32_t*)take(ncap * 4);
     t.big = (uint32_t*)take(3 * nc * 4);
     t.cellof = (int32_t*)take(ncap * 4);
@@ -1457,6 +1606,15 @@ size_t layout(const pic_rz_config* c, const int64_t cap[3], char* base, Work* w)
     t.ve = (double*)take((size_t)cap[2] * 48);
     t.iflag = (uint8_t*)take((size_t)cap[1]);
     t.vei = (double*)take((size_t)cap[1] * 24);
+    t.pkey = (unsigned long long*)take(nprod * 8 + 8);
+    t.pslot = (uint32_t*)take(nprod * 4 + 4);
+    t.tr = (double*)take(capmax * 8);
+    t.tz = (double*)take(capmax * 8);
+    t.tvr = (double*)take(capmax * 8);
+    t.tvt = (double*)take(capmax * 8);
+    t.tvz = (double*)take(capmax * 8);
+    t.tid = (uint32_t*)take(capmax * 4);
+    t.tcharge = (uint8_t*)take(capmax);
     t.pci = (uint32_t*)take(nprod * 4 + 4);
     t.pce = (uint32_t*)take(nprod * 4 + 4);
     t.ppi = (uint32_t*)take(nprod * 4 + 4);
@@ -1494,6 +1652,7 @@ const char* check(const pic_rz_config* c) {
         return "collisions need 0 < xs_emin < xs_emax and xi > 0";
     if (c->fn_rings < 0 || c->fn_rings > (1 << 20)) return "fn_rings out of range";
     if (c->cu2 != 0 && c->cu2 != 1) return "cu2 must be 0 or 1";
+    if (c->sort_every < 0) return "sort_every must be >= 0";
     if (c->cu2 && !(c->xs_n > 0 && c->xi2 > 0)) return "Cu2+ needs the five tables and xi2 > 0";
     if (c->fn_rings > 0 && !(c->phi_w > 0 && c->tip_r > 0)) return "emission needs phi_w > 0 and a tip";
     return nullptr;
@@ -1732,6 +1891,7 @@ CollArgs coll_args(pic_rz_ctx* c, uint32_t step) {
     a.crank = c->w.crank;
     a.start = c->w.start;
     a.seg = c->w.seg;
+    a.segid = c->w.segid;
     a.sorted = c->w.sorted;
     a.big = c->w.big;
     a.cellof = c->w.cellof;
@@ -1741,10 +1901,13 @@ CollArgs coll_args(pic_rz_ctx* c, uint32_t step) {
     a.iflag = c->w.iflag;
     a.vei = c->w.vei;
     a.charge = c->cfg.cu2 ? c->buf.charge : nullptr;
+    a.pkey = c->w.pkey;
+    a.pslot = c->w.pslot;
     a.pci = c->w.pci;
     a.pce = c->w.pce;
     a.ppi = c->w.ppi;
     a.ppe = c->w.ppe;
+    a.pcap = c->buf.cap[1] + c->buf.cap[2];
     a.cu2 = c->cfg.cu2;
     a.xi2 = c->cfg.xi2;
     a.E = c->buf.field;
@@ -1783,9 +1946,8 @@ void scan_u32(pic_rz_ctx* c, const uint32_t* in, uint32_t* out, int64_t m) {
                        (const uint32_t*)c->w.spre);
 }
 
-// (e, Cu) pairs, (Cu+, Cu) pairs, field ionization, then the products
-void collide(pic_rz_ctx* c, uint32_t step) {
-    CollArgs a = coll_args(c, step);
+// grouping by (species, cell), ascending id within a cell
+void group(pic_rz_ctx* c, const CollArgs& a) {
     const int64_t ncap = c->buf.cap[0] + c->buf.cap[1] + c->buf.cap[2];
     hipLaunchKernelGGL(k_zero_u32, dim3(grid_of(3 * a.nc)), dim3(kBlock), 0, c->stream, a.cnt, 3 * a.nc, c->st);
     for (int s = 0; s < 3; ++s)
@@ -1797,6 +1959,48 @@ void collide(pic_rz_ctx* c, uint32_t step) {
             hipLaunchKernelGGL(k_place, dim3(grid_of(c->buf.cap[s])), dim3(kBlock), 0, c->stream, a, s);
     hipLaunchKernelGGL(k_rank, dim3(grid_of(ncap)), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(k_sort_big, dim3(kBigBlocks), dim3(kBlock), 0, c->stream, a);
+}
+
+// every species in the grouping's order (cell, then id), freed slots dropped
+void reorder(pic_rz_ctx* c, const CollArgs& a) {
+    for (int s = 0; s < 3; ++s) {
+        if (c->buf.cap[s] == 0) continue;
+        ReorderArgs r;
+        r.r = c->buf.r[s];
+        r.z = c->buf.z[s];
+        r.vr = c->buf.vr[s];
+        r.vt = c->buf.vt[s];
+        r.vz = c->buf.vz[s];
+        r.id = c->buf.id[s];
+        r.charge = (s == 1 && c->cfg.cu2) ? c->buf.charge : nullptr;
+        r.tr = c->w.tr;
+        r.tz = c->w.tz;
+        r.tvr = c->w.tvr;
+        r.tvt = c->w.tvt;
+        r.tvz = c->w.tvz;
+        r.tid = c->w.tid;
+        r.tcharge = c->w.tcharge;
+        r.sorted = a.sorted;
+        r.start = a.start;
+        r.first = s * a.nc;
+        r.next = s < 2 ? (s + 1) * a.nc : -1;
+        r.st = c->st;
+        const unsigned G = grid_of(c->buf.cap[s]);
+        hipLaunchKernelGGL(k_reorder_gather, dim3(G), dim3(kBlock), 0, c->stream, r);
+        hipLaunchKernelGGL(k_reorder_back, dim3(G), dim3(kBlock), 0, c->stream, r, s);
+    }
+}
+
+// (e, Cu) pairs, (Cu+, Cu) pairs, (e, Cu+) pairs with Cu2+, field
+// ionization, then the products; every sort_every steps the particles are
+// reordered by cell first (and grouped again)
+void collide(pic_rz_ctx* c, uint32_t step) {
+    CollArgs a = coll_args(c, step);
+    group(c, a);
+    if (c->cfg.sort_every > 0 && step % (uint32_t)c->cfg.sort_every == 0) {
+        reorder(c, a);
+        group(c, a);
+    }
     if (c->buf.cap[0] > 0)
         hipLaunchKernelGGL(k_pair, dim3(grid_of(c->buf.cap[0])), dim3(kBlock), 0, c->stream, a, 1);
     if (c->buf.cap[1] > 0)
@@ -1804,13 +2008,14 @@ void collide(pic_rz_ctx* c, uint32_t step) {
     if (c->cfg.cu2 && c->buf.cap[0] > 0 && c->buf.cap[1] > 0)
         hipLaunchKernelGGL(k_pair, dim3(grid_of(c->buf.cap[0])), dim3(kBlock), 0, c->stream, a, 3);
     if (c->buf.cap[2] > 0) hipLaunchKernelGGL(k_fi, dim3(grid_of(c->buf.cap[2])), dim3(kBlock), 0, c->stream, a);
-    const int64_t L = 2 * c->buf.cap[2] + c->buf.cap[1];
-    if (L == 0) return;
-    hipLaunchKernelGGL(k_prod_counts, dim3(grid_of(L)), dim3(kBlock), 0, c->stream, a, L);
-    scan_u32(c, a.pci, a.ppi, L);
-    scan_u32(c, a.pce, a.ppe, L);
-    hipLaunchKernelGGL(k_prod_commit, dim3(1), dim3(64), 0, c->stream, a, L);
-    hipLaunchKernelGGL(k_prod_place, dim3(grid_of(L)), dim3(kBlock), 0, c->stream, a, L);
+    if (a.pcap == 0) return;
+    hipLaunchKernelGGL(k_prod_list, dim3(grid_of(a.pcap)), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(k_prod_sort, dim3(1), dim3(1024), 0, c->stream, a);
+    hipLaunchKernelGGL(k_prod_counts, dim3(grid_of(a.pcap)), dim3(kBlock), 0, c->stream, a);
+    scan_u32(c, a.pci, a.ppi, a.pcap);
+    scan_u32(c, a.pce, a.ppe, a.pcap);
+    hipLaunchKernelGGL(k_prod_commit, dim3(1), dim3(64), 0, c->stream, a);
+    hipLaunchKernelGGL(k_prod_place, dim3(grid_of(a.pcap)), dim3(kBlock), 0, c->stream, a);
 }
 
 // Fowler-Nordheim emission from the rings of the tip

@@ -21,7 +21,7 @@ PIC_RZ_ALL = 111
 class pic_rz_config(C.Structure):
     _fields_ = [("nr", C.c_int32), ("nz", C.c_int32), ("h", C.c_double), ("tip_r", C.c_double),
                 ("tip_h", C.c_double), ("apex_field", C.c_double), ("dt", C.c_double), ("m_ion", C.c_double),
-                ("laplace_rtol", C.c_double), ("maxit", C.c_int32), ("reserved", C.c_int32),
+                ("laplace_rtol", C.c_double), ("maxit", C.c_int32), ("sort_every", C.c_int32),
                 ("step_rtol", C.c_double), ("seed", C.c_uint64), ("xi", C.c_double), ("phi_w", C.c_double),
                 ("xs_emin", C.c_double), ("xs_emax", C.c_double), ("xs_n", C.c_int32), ("fn_rings", C.c_int32),
                 ("cu2", C.c_int32), ("reserved3", C.c_int32), ("xi2", C.c_double)]
@@ -114,11 +114,12 @@ class RZSimulation:
 
     def __init__(self, nr, nz, h, tip_r, tip_h, apex_field, dt, m_ion, load, caps=None, laplace_rtol=1e-13,
                  step_rtol=1e-10, maxit=100000, device="cuda", seed=1, xs=None, xi=7.726380, phi_w=4.5,
-                 fn_rings=0, ids=None, cu2=False, xi2=20.29239):
+                 fn_rings=0, ids=None, cu2=False, xi2=20.29239, sort_every=0):
         self.device = torch.device(device)
         self.cfg = pic_rz_config(nr=nr, nz=nz, h=h, tip_r=tip_r, tip_h=tip_h, apex_field=apex_field, dt=dt,
                                  m_ion=m_ion, laplace_rtol=laplace_rtol, maxit=maxit, step_rtol=step_rtol,
-                                 seed=seed, xi=xi, phi_w=phi_w, fn_rings=fn_rings, cu2=1 if cu2 else 0, xi2=xi2)
+                                 seed=seed, xi=xi, phi_w=phi_w, fn_rings=fn_rings, cu2=1 if cu2 else 0, xi2=xi2,
+                                 sort_every=sort_every)
         self.xs = None
         if xs is not None:
             self.cfg.xs_emin, self.cfg.xs_emax = xs[0], xs[1]
@@ -184,12 +185,13 @@ class RZSimulation:
         return pic_rz_moments(self.ctx)
 
     def state(self):
-        """Alive particles of each species in slot order (= id order)."""
+        """Alive particles of each species in ascending id order."""
         n = self.moments()["n_slots"]
         out = []
         for s in range(3):
             ids = self.sp[s]["id"][: n[s]].cpu().numpy().view(np.uint32)
-            alive = ids != DEAD
+            alive = np.flatnonzero(ids != DEAD)
+            alive = alive[np.argsort(ids[alive], kind="stable")]
             d = {k: self.sp[s][k][: n[s]].cpu().numpy()[alive] for k in ("r", "z", "vr", "vt", "vz")}
             d["id"] = ids[alive]
             if s == 1 and self.charge is not None:
