@@ -269,6 +269,7 @@ def main():
                     help="the axisymmetric variant on the paper's geometry: every stage of its step")
     ap.add_argument("--rz-scale", type=float, default=1.0, help="scale factor of the axisymmetric particle counts")
     ap.add_argument("--rz-iters", action="store_true", help="with --rz: read the CG iterations after every step")
+    ap.add_argument("--rz-sort-every", type=int, default=16, help="with --rz: reorder period of the particles")
     ap.add_argument("--pmc-out", default=TRAFFIC_FILE, help="where --pmc-summary writes its JSON")
     ap.add_argument("--pmc-summary", nargs=5, metavar=("FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV",
                                                         "COPY_MIB"),
@@ -797,7 +798,7 @@ def rz_main(args, log):
     caps = [int(1.25 * counts[0]) + 65536, int(1.25 * counts[1]) + 4096, counts[2] + 1]
     keys = ("nr", "nz", "h", "tip_r", "tip_h", "apex_field", "dt", "m_ion")
     sim = rz.RZSimulation(**{k: geo[k] for k in keys}, load=load, caps=caps, step_rtol=1e-8, seed=geo["seed"],
-                          xs=geo["xs"], fn_rings=geo["fn_rings"], cu2=geo["cu2"])
+                          xs=geo["xs"], fn_rings=geo["fn_rings"], cu2=geo["cu2"], sort_every=args.rz_sort_every)
     del load
     log(f"[bench] rz instance ready ({time.perf_counter() - t0:.1f} s), {sum(counts)} particles")
     sim.step(1, rz.PIC_RZ_DEPOSIT | rz.PIC_RZ_SOLVE)
@@ -852,6 +853,7 @@ def rz_main(args, log):
         "warmup": args.warmup, "ms_per_step": 1e3 * wall / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "rz_context", "grid": [geo["nr"], geo["nz"]], "h_nm": geo["h"] * 1e9,
+                   "sort_every": args.rz_sort_every,
                    "tip_r_nm": geo["tip_r"] * 1e9, "tip_h_um": geo["tip_h"] * 1e6, "particles": list(counts)},
         "roofline": {"bound": "hbm", "kernel": "k_push (all species, one pass)", "achieved": ach, "peak": 8000.0,
                      "unit": "GB/s", "frac": ach / 8000.0, "traffic": traffic,

@@ -633,12 +633,29 @@ __global__ void k_qsum(const int64_t* rho, int64_t nn, unsigned long long* out) 
 
 // ---------------------------------------------------------------------------
 // Initial ids: none free; next_id one above the largest.
-__global__ void k_check_ids(const uint32_t* id, int64_t n, State* st) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const uint32_t v = id[p];
-    if (v == kDead) atomicOr(&st->skip, 1);
-    else atomicMax(&st->next_id, (unsigned long long)v + 1ull);
+__global__ __launch_bounds__(kBlock) void k_check_ids(const uint32_t* id, int64_t n, State* st) {
+    __shared__ unsigned long long wm[kBlock / 64];
+    // grid-stride: the largest id + 1 with one atomic per block
+    unsigned long long m = 0;
+    int bad = 0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = id[p];
+        if (v == kDead) bad = 1;
+        else m = (unsigned long long)v + 1ull > m ? (unsigned long long)v + 1ull : m;
+    }
+    if (bad) atomicOr(&st->skip, 1);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long y = __shfl_xor(m, o, 64);
+        m = y > m ? y : m;
+    }
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) m = wm[w] > m ? wm[w] : m;
+        m = wm[0] > m ? wm[0] : m;
+        if (m) atomicMax(&st->next_id, m);
+    }
 }
 
 // Initial ion charge states: 1 or 2.
@@ -799,15 +816,30 @@ __device__ inline int cell_index(const Geo& g, double r, double z) {
     return k * (g.nr - 1) + i;
 }
 
-// cell of every slot in use, counts per (species, cell); clears the flags
+// cell of every slot in use, counts per (species, cell) and each particle's
+// arrival place in its cell; clears the flags. Consecutive lanes of a
+// wavefront in one cell (the common case after a reorder) take their places
+// with one atomic for the run.
 __global__ __launch_bounds__(kBlock) void k_cells(CollArgs a, int s) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= (int64_t)a.st->n[s]) return;
+    const bool in = p < (int64_t)a.st->n[s];
     int32_t c = -1;
-    if (a.id[s][p] != kDead) {
-        c = cell_index(a.g, a.r[s][p], a.z[s][p]);
-        a.cpos[a.off[s] + p] = atomicAdd(&a.cnt[s * a.nc + c], 1u);
-    }
+    if (in && a.id[s][p] != kDead) c = cell_index(a.g, a.r[s][p], a.z[s][p]);
+    const int lane = threadIdx.x & 63;
+    const int32_t prev = __shfl_up(c, 1, 64);
+    const bool head = lane == 0 || prev != c;
+    const uint64_t heads = __ballot(head);
+    // the run of this lane: from its head (the highest head at or below it)
+    // to the next head
+    const uint64_t below = heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull));
+    const int start = 63 - __builtin_clzll(below);
+    const uint64_t above = lane == 63 ? 0ull : (heads >> (lane + 1));
+    const int next = above ? lane + 1 + __builtin_ctzll(above) : 64;
+    uint32_t base = 0;
+    if (head && c >= 0) base = atomicAdd(&a.cnt[s * a.nc + c], (uint32_t)(next - lane));
+    base = __shfl(base, start, 64);
+    if (!in) return;
+    if (c >= 0) a.cpos[a.off[s] + p] = base + (uint32_t)(lane - start);
     a.cellof[a.off[s] + p] = c;
     a.used[a.off[s] + p] = 0;
     if (s == 2) a.pflag[p] = 0;
@@ -2117,8 +2149,8 @@ pic_status pic_rz_init(const pic_rz_config* cfg, const pic_rz_buffers* bufs, voi
     pic_status s = hip_ok(c, hipMemcpyAsync(c->st, &h0, sizeof(State), hipMemcpyHostToDevice, c->stream), "copy");
     for (int sp = 0; sp < 3 && s == PIC_OK; ++sp)
         if (bufs->n[sp] > 0)
-            hipLaunchKernelGGL(k_check_ids, dim3(grid_of(bufs->n[sp])), dim3(kBlock), 0, c->stream, bufs->id[sp],
-                               bufs->n[sp], c->st);
+            hipLaunchKernelGGL(k_check_ids, dim3(std::min<unsigned>(1024u, grid_of(bufs->n[sp]))), dim3(kBlock), 0,
+                               c->stream, bufs->id[sp], bufs->n[sp], c->st);
     if (s == PIC_OK && cfg->cu2 && bufs->n[1] > 0)
         hipLaunchKernelGGL(k_check_charge, dim3(grid_of(bufs->n[1])), dim3(kBlock), 0, c->stream,
                            (const uint8_t*)bufs->charge, bufs->n[1], c->st);
