@@ -74,10 +74,18 @@ __device__ inline void couplings(int i, int nr, double& cin, double& cout, doubl
     cax = hi * hi - lo * lo;
 }
 
+// (i, k) of node n = k nr + i (grids hold fewer than 2^31 nodes: 32-bit division)
+__device__ inline void node_ik(int64_t n, int nr, int& i, int& k) {
+    const unsigned u = (unsigned)n, d = (unsigned)nr, q = u / d;
+    k = (int)q;
+    i = (int)(u - q * d);
+}
+
 __global__ void k_types(Geo g, uint8_t* type) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= (int64_t)g.nr * g.nz) return;
-    const int i = (int)(n % g.nr), k = (int)(n / g.nr);
+    int i, k;
+    node_ik(n, g.nr, i, k);
     uint8_t t = kFree;
     if (inside_tip(g, (double)i, (double)k)) t = kHeld0;
     if (k == 0) t = kHeld0;
@@ -87,7 +95,7 @@ __global__ void k_types(Geo g, uint8_t* type) {
 
 // sum_j c (x_n - x_m) at a free node n (x of held neighbours as given)
 __device__ inline double apply_at(const Geo& g, const double* x, int64_t n) {
-    const int i = (int)(n % g.nr);
+    const int i = (int)((unsigned)n % (unsigned)g.nr);
     double cin, cout, cax;
     couplings(i, g.nr, cin, cout, cax);
     const double xn = x[n];
@@ -132,6 +140,21 @@ __device__ inline void block_reduce2(double a, double b, double* part) {
     }
 }
 
+// sum over the blocks b of part[2 b + off] by one wavefront (four loads a
+// lane issued together, then a butterfly): every lane, and every block that
+// calls it, gets the same bits
+__device__ inline double wave_partials(const double* part, int off) {
+    static_assert(kCgBlocks % 64 == 0, "kCgBlocks must be a multiple of 64");
+    const int lane = threadIdx.x & 63;
+    double t[kCgBlocks / 64];
+#pragma unroll
+    for (int u = 0; u < kCgBlocks / 64; ++u) t[u] = part[2 * (lane + 64 * u) + off];
+    double v = 0.0;
+#pragma unroll
+    for (int u = 0; u < kCgBlocks / 64; ++u) v += t[u];
+    return pic::wave_sum(v);
+}
+
 // phi at held nodes to their values; r = b - A phi on free nodes; partials
 // of r.r and of the right-hand side with the held values moved over
 __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs a) {
@@ -149,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs a) {
     // so a held neighbour's value is formed from its type
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (int64_t)gridDim.x * blockDim.x) {
         if (a.type[n] != kFree) continue;
-        const int i = (int)(n % a.g.nr);
+        const int i = (int)((unsigned)n % (unsigned)a.g.nr);
         double cin, cout, cax;
         couplings(i, a.g.nr, cin, cout, cax);
         const double b = (double)a.rho[n] * a.qscale;
@@ -174,14 +197,10 @@ __global__ __launch_bounds__(kBlock) void k_cg_init(CgArgs a) {
     block_reduce2(rr, bb, a.part);
 }
 
-// (single block) rr, bb from the partials
+// (one wavefront) rr, bb from the partials
 __global__ void k_cg_start(CgArgs a, double rtol, int maxit) {
+    const double rr = wave_partials(a.part, 0), bb = wave_partials(a.part, 1);
     if (threadIdx.x == 0) {
-        double rr = 0.0, bb = 0.0;
-        for (int b = 0; b < kCgBlocks; ++b) {
-            rr += a.part[2 * b];
-            bb += a.part[2 * b + 1];
-        }
         State* st = a.st;
         st->rr = rr;
         st->bb = bb;
@@ -211,10 +230,9 @@ __global__ __launch_bounds__(kBlock) void k_cg_ap(CgArgs a) {
 __global__ __launch_bounds__(kBlock) void k_cg_update(CgArgs a) {
     if (a.st->done) return;
     __shared__ double alpha;
-    if (threadIdx.x == 0) {
-        double pq = 0.0;
-        for (int b = 0; b < kCgBlocks; ++b) pq += a.part[2 * b];
-        alpha = a.st->rz / pq;
+    if (threadIdx.x < 64) {
+        const double pq = wave_partials(a.part, 0);
+        if (threadIdx.x == 0) alpha = a.st->rz / pq;
     }
     __syncthreads();
     const int64_t nn = (int64_t)a.g.nr * a.g.nz;
@@ -229,13 +247,12 @@ __global__ __launch_bounds__(kBlock) void k_cg_update(CgArgs a) {
     block_reduce2(rr, 0.0, a.part + 2 * kCgBlocks);
 }
 
-// (single block) r.r from the partials, convergence
+// (one wavefront) r.r from the partials, convergence
 __global__ void k_cg_check(CgArgs a) {
-    if (threadIdx.x != 0) return;
     State* st = a.st;
     if (st->done) return;
-    double rr = 0.0;
-    for (int b = 0; b < kCgBlocks; ++b) rr += a.part[2 * kCgBlocks + 2 * b];
+    const double rr = wave_partials(a.part + 2 * kCgBlocks, 0);
+    if (threadIdx.x != 0) return;
     st->rr = rr;
     st->it += 1;
     if (rr <= st->rtol * st->rtol * st->bb || st->it >= st->maxit) st->done = 1;
@@ -255,13 +272,12 @@ __global__ __launch_bounds__(kBlock) void k_pcg_rz(CgArgs a, int first) {
     block_reduce2(rz, 0.0, a.part);
 }
 
-// (single block) beta = r.z / previous r.z (first: only r.z)
+// (one wavefront) beta = r.z / previous r.z (first: only r.z)
 __global__ void k_pcg_beta(CgArgs a, int first) {
-    if (threadIdx.x != 0) return;
     State* st = a.st;
     if (st->done) return;
-    double rz = 0.0;
-    for (int b = 0; b < kCgBlocks; ++b) rz += a.part[2 * b];
+    const double rz = wave_partials(a.part, 0);
+    if (threadIdx.x != 0) return;
     st->beta = first ? 0.0 : rz / st->rz;
     st->rz = rz;
 }
@@ -278,19 +294,23 @@ __global__ __launch_bounds__(kBlock) void k_cg_p(CgArgs a) {
 // Multigrid preconditioner of the CG: one V-cycle z = M r of the error
 // equation (held nodes at zero). Level l has nr_l x nz_l nodes; a dimension
 // is halved (node I of the coarse level at node 2 I of the finer) while its
-// cell count is even and at least 4; the coarse operator is the same finite
+// cell count is even and at least 4, until a level has at most kMgDirectMax
+// nodes; the coarse operator is the same finite
 // volume discretization at the coarse spacings H_r = 2^a h, H_z = 2^b h,
 // in units of pi eps0 h: radial couplings 2^b 2 (I -+ 1/2), axial couplings
 // 2^(2a-b) (r_hi^2 - r_lo^2) in coarse index units. A coarse node is held if
 // the finer node at its place is. Prolongation is bilinear, restriction its
 // transpose (the residual is an integrated charge, so it is summed). Damped
 // Jacobi (omega = 4/5) smooths, two sweeps before and two after; the coarsest
-// level, when it has at most kMgCoarseMax nodes, is swept kMgCoarseSweeps
-// times in LDS by one block (otherwise it is smoothed like the others). The
-// cycle is a fixed symmetric linear operator, as CG needs.
+// level is solved exactly when it has at most kMgDirectMax nodes (its inverse
+// from the set-up), else (a level that cannot be halved further) swept
+// kMgCoarseSweeps times from zero in LDS when it has at most kMgCoarseMax
+// nodes, else smoothed like the others. The cycle is a fixed symmetric linear
+// operator, as CG needs.
 constexpr int kMgMaxLevels = 16;
 constexpr int kMgCoarseMax = 2048;
 constexpr int kMgCoarseSweeps = 64;
+constexpr int kMgDirectMax = 64;  // the coarsening stops at this many nodes; such a level is solved exactly
 constexpr double kMgOmega = 0.8;
 
 struct Lv {
@@ -299,25 +319,45 @@ struct Lv {
     const uint8_t* type;  // 0 free
 };
 
-// sum_j c (x_n - x_m) over the neighbours (held ones at zero) and the diagonal
-__device__ inline double lv_apply(const Lv& L, const double* x, int64_t n, double& diag) {
-    const int i = (int)(n % L.nr), k = (int)(n / L.nr);
+// sum_j c (x_n - x_m) over the neighbours (held ones at zero) and the
+// diagonal, at node n = (i, k); xv(m, i, k) gives the value of node m = (i, k)
+template <class X>
+__device__ inline double lv_apply_f(const Lv& L, int64_t n, int i, int k, double& diag, X xv) {
     const double cin = i > 0 ? L.fr * 2.0 * (i - 0.5) : 0.0;
     const double cout = i < L.nr - 1 ? L.fr * 2.0 * (i + 0.5) : 0.0;
     const double hi = fmin(i + 0.5, L.nr - 1.0), lo = fmax(i - 0.5, 0.0);
     const double cax = L.fa * (hi * hi - lo * lo);
-    const double xn = x[n];
+    const double xn = xv(n, i, k);
     double s = 0.0;
-    if (cin != 0.0 && L.type[n - 1] == kFree) s -= cin * x[n - 1];
-    if (cout != 0.0 && L.type[n + 1] == kFree) s -= cout * x[n + 1];
-    if (k > 0 && L.type[n - L.nr] == kFree) s -= cax * x[n - L.nr];
-    if (k < L.nz - 1 && L.type[n + L.nr] == kFree) s -= cax * x[n + L.nr];
+    if (cin != 0.0 && L.type[n - 1] == kFree) s -= cin * xv(n - 1, i - 1, k);
+    if (cout != 0.0 && L.type[n + 1] == kFree) s -= cout * xv(n + 1, i + 1, k);
+    if (k > 0 && L.type[n - L.nr] == kFree) s -= cax * xv(n - L.nr, i, k - 1);
+    if (k < L.nz - 1 && L.type[n + L.nr] == kFree) s -= cax * xv(n + L.nr, i, k + 1);
     diag = cin + cout + 2.0 * cax;
     return s + diag * xn;
 }
 
+__device__ inline double lv_apply(const Lv& L, const double* x, int64_t n, int i, int k, double& diag) {
+    return lv_apply_f(L, n, i, k, diag, [&](int64_t m, int, int) { return x[m]; });
+}
+
+__device__ inline double lv_apply(const Lv& L, const double* x, int64_t n, double& diag) {
+    int i, k;
+    node_ik(n, L.nr, i, k);
+    return lv_apply(L, x, n, i, k, diag);
+}
+
+// the diagonal of a node of column i
+__device__ inline double lv_diag(const Lv& L, int i) {
+    const double cin = i > 0 ? L.fr * 2.0 * (i - 0.5) : 0.0;
+    const double cout = i < L.nr - 1 ? L.fr * 2.0 * (i + 0.5) : 0.0;
+    const double hi = fmin(i + 0.5, L.nr - 1.0), lo = fmax(i - 0.5, 0.0);
+    const double cax = L.fa * (hi * hi - lo * lo);
+    return cin + cout + 2.0 * cax;
+}
+
 // The level operations over nodes n0, n0 + stride, ... (a grid-stride loop
-// in the kernels of one level, a block-stride loop in k_mg_small).
+// in the kernels of one level, a block-stride loop in k_mg_lds).
 
 // y = x + omega D^-1 (b - A x) at free nodes (zero_x: x taken as zero)
 __device__ inline void mg_jacobi(const Lv& L, const double* x, double* y, const double* b, int zero_x, int64_t n0,
@@ -352,19 +392,14 @@ __global__ __launch_bounds__(kBlock) void k_mg_jacobi(Lv L, const double* x, dou
     mg_jacobi(L, x, y, b, zero_x, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
 }
 
-__global__ __launch_bounds__(kBlock) void k_mg_resid(Lv L, const double* x, const double* b, double* t,
-                                                      const State* st) {
-    if (st->done) return;
-    mg_resid(L, x, b, t, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, (int64_t)gridDim.x * blockDim.x);
-}
-
 // b_c = R t (sr, sz: 2 where the dimension is halved, else 1)
 __device__ inline void mg_restrict(const Lv& F, const Lv& Cl, const double* t, double* bc, int sr, int sz,
                                    int64_t n0, int64_t stride) {
     const int64_t nn = (int64_t)Cl.nr * Cl.nz;
     for (int64_t n = n0; n < nn; n += stride) {
         if (Cl.type[n] != kFree) continue;
-        const int I = (int)(n % Cl.nr), K = (int)(n / Cl.nr);
+        int I, K;
+        node_ik(n, Cl.nr, I, K);
         const int i0 = sr * I, k0 = sz * K;
         double s = 0.0;
         for (int dk = -(sz - 1); dk <= sz - 1; ++dk) {
@@ -383,20 +418,14 @@ __device__ inline void mg_restrict(const Lv& F, const Lv& Cl, const double* t, d
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_mg_restrict(Lv F, Lv Cl, const double* t, double* bc, int sr, int sz,
-                                                         const State* st) {
-    if (st->done) return;
-    mg_restrict(F, Cl, t, bc, sr, sz, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
-                (int64_t)gridDim.x * blockDim.x);
-}
-
 // x_f += P x_c at free fine nodes
 __device__ inline void mg_prolong(const Lv& F, const Lv& Cl, const double* xc, double* xf, int sr, int sz,
                                   int64_t n0, int64_t stride) {
     const int64_t nn = (int64_t)F.nr * F.nz;
     for (int64_t n = n0; n < nn; n += stride) {
         if (F.type[n] != kFree) continue;
-        const int i = (int)(n % F.nr), k = (int)(n / F.nr);
+        int i, k;
+        node_ik(n, F.nr, i, k);
         int I0 = i, I1 = i, K0 = k, K1 = k;
         if (sr == 2) {
             I0 = i >> 1;
@@ -421,11 +450,111 @@ __device__ inline void mg_prolong(const Lv& F, const Lv& Cl, const double* xc, d
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_mg_prolong(Lv F, Lv Cl, const double* xc, double* xf, int sr, int sz,
-                                                        const State* st) {
+// Fused level kernels of the large levels (one launch instead of two or
+// three; the values of every node are those of the separate passes).
+
+// y = two sweeps from zero: the first sweep's value omega b_m / d_m is formed
+// at the node and its neighbours
+__global__ __launch_bounds__(kBlock) void k_mg_smooth2(Lv L, const double* b, double* y, const State* st) {
     if (st->done) return;
-    mg_prolong(F, Cl, xc, xf, sr, sz, (int64_t)blockIdx.x * blockDim.x + threadIdx.x,
-               (int64_t)gridDim.x * blockDim.x);
+    const int64_t nn = (int64_t)L.nr * L.nz;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (int64_t)gridDim.x * blockDim.x) {
+        if (L.type[n] != kFree) continue;
+        int i, k;
+        node_ik(n, L.nr, i, k);
+        double d;
+        const double ax =
+            lv_apply_f(L, n, i, k, d, [&](int64_t m, int im, int) { return kMgOmega * b[m] / lv_diag(L, im); });
+        const double x1 = kMgOmega * b[n] / d;
+        y[n] = x1 + kMgOmega * (b[n] - ax) / d;
+    }
+}
+
+// b_c = R (b - A x): the residual formed at each fine node the restriction reads
+__global__ __launch_bounds__(kBlock) void k_mg_resid_restrict(Lv F, Lv Cl, const double* x, const double* b,
+                                                               double* bc, int sr, int sz, const State* st) {
+    if (st->done) return;
+    const int64_t nn = (int64_t)Cl.nr * Cl.nz;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (int64_t)gridDim.x * blockDim.x) {
+        if (Cl.type[n] != kFree) continue;
+        int I, K;
+        node_ik(n, Cl.nr, I, K);
+        const int i0 = sr * I, k0 = sz * K;
+        double s = 0.0;
+        for (int dk = -(sz - 1); dk <= sz - 1; ++dk) {
+            const int k = k0 + dk;
+            if (k < 0 || k >= F.nz) continue;
+            const double wk = dk == 0 ? 1.0 : 0.5;
+            for (int di = -(sr - 1); di <= sr - 1; ++di) {
+                const int i = i0 + di;
+                if (i < 0 || i >= F.nr) continue;
+                const double wi = di == 0 ? 1.0 : 0.5;
+                const int64_t m = (int64_t)k * F.nr + i;
+                if (F.type[m] != kFree) continue;
+                double d;
+                const double t = b[m] - lv_apply(F, x, m, i, k, d);
+                s += wi * wk * t;
+            }
+        }
+        bc[n] = s;
+    }
+}
+
+// the bilinear correction P x_c at fine node n (free)
+__device__ inline double mg_corr(const Lv& Cl, const double* xc, int sr, int sz, int i, int k) {
+    int I0 = i, I1 = i, K0 = k, K1 = k;
+    if (sr == 2) {
+        I0 = i >> 1;
+        I1 = (i + 1) >> 1;
+    }
+    if (sz == 2) {
+        K0 = k >> 1;
+        K1 = (k + 1) >> 1;
+    }
+    const double wi = I0 == I1 ? 1.0 : 0.5, wk = K0 == K1 ? 1.0 : 0.5;
+    auto at = [&](int I, int K) {
+        const int64_t m = (int64_t)K * Cl.nr + I;
+        return Cl.type[m] == kFree ? xc[m] : 0.0;
+    };
+    double v = at(I0, K0);
+    if (I1 != I0) v += at(I1, K0);
+    if (K1 != K0) {
+        v += at(I0, K1);
+        if (I1 != I0) v += at(I1, K1);
+    }
+    return wi * wk * v;
+}
+
+// y = one sweep from x + P x_c (the corrected value formed at the node and
+// its neighbours; x itself is not written)
+__global__ __launch_bounds__(kBlock) void k_mg_prolong_smooth(Lv F, Lv Cl, const double* xc, const double* x,
+                                                               double* y, const double* b, int sr, int sz,
+                                                               const State* st) {
+    if (st->done) return;
+    const int64_t nn = (int64_t)F.nr * F.nz;
+    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (int64_t)gridDim.x * blockDim.x) {
+        if (F.type[n] != kFree) continue;
+        int i, k;
+        node_ik(n, F.nr, i, k);
+        auto xv = [&](int64_t m, int im, int km) { return x[m] + mg_corr(Cl, xc, sr, sz, im, km); };
+        double d;
+        const double ax = lv_apply_f(F, n, i, k, d, xv);
+        y[n] = xv(n, i, k) + kMgOmega * (b[n] - ax) / d;
+    }
+}
+
+// x = A_c^-1 b on the coarsest level from its inverse (nc x nc, zero rows and
+// columns at held nodes), at free nodes; the sum in column order
+__device__ inline void mg_direct(const Lv& C, const double* inv, const double* b, double* x, int64_t n0,
+                                 int64_t stride) {
+    const int nc = C.nr * C.nz;
+    for (int64_t j = n0; j < nc; j += stride) {
+        if (C.type[j] != kFree) continue;
+        double s = 0.0;
+        for (int k = 0; k < nc; ++k)
+            if (C.type[k] == kFree) s += inv[j * nc + k] * b[k];
+        x[j] = s;
+    }
 }
 
 // the coarsest level: kMgCoarseSweeps Jacobi sweeps from zero, in LDS, one block
@@ -450,68 +579,101 @@ __device__ inline void mg_coarse(const Lv& L, const double* b, double* x, double
     for (int n = threadIdx.x; n < nn; n += blockDim.x) x[n] = xs[cur][n];
 }
 
-__global__ __launch_bounds__(kBlock) void k_mg_coarse(Lv L, const double* b, double* x, const State* st) {
+__global__ __launch_bounds__(kBlock) void k_mg_coarse(Lv L, const double* b, double* x, const double* inv,
+                                                       const State* st) {
     if (st->done) return;
     __shared__ double xs[2][kMgCoarseMax];
-    mg_coarse(L, b, x, xs);
+    if (inv) mg_direct(L, inv, b, x, threadIdx.x, blockDim.x);
+    else mg_coarse(L, b, x, xs);
 }
 
-// The levels from l0 down, when level l0 has at most kMgSmallNodes nodes:
-// the whole V-cycle below the caller in one block of kMgSmallBlock threads,
-// the phases separated by barriers (the arrays are the block's own).
-constexpr int kMgSmallNodes = 2048;
-constexpr int kMgSmallBlock = 1024;
+// The levels from l0 down in one block with every vector in LDS, when their
+// nodes add up to at most kMgLdsNodes (separate launches per level cost more
+// than the whole work of these levels): the right-hand side of level l0 is
+// read once, its x_b written once at the end, and each phase is one pass of
+// the block over a level's nodes between barriers. The arithmetic of every
+// node is that of the level kernels; the residual of a level is kept in its
+// x_a, free after the pre-smoothing.
+constexpr int kMgLdsNodes = 2560;
+constexpr int kMgLdsBlock = 1024;
 
-struct MgSmall {
+struct MgLds {
     int l0, levels;
-    Lv lv[kMgMaxLevels];
-    const double* b[kMgMaxLevels];
-    double *xa[kMgMaxLevels], *xb[kMgMaxLevels], *t[kMgMaxLevels], *bw[kMgMaxLevels];
-    int sr[kMgMaxLevels], sz[kMgMaxLevels];
+    Lv lv[kMgMaxLevels];  // node types in global memory
+    int off[kMgMaxLevels], sr[kMgMaxLevels], sz[kMgMaxLevels];
+    const double* b;    // level l0
+    double* x;          // level l0 (x_b), written at free nodes
+    const double* inv;  // inverse of the coarsest operator, or null (sweeps)
 };
 
-__global__ __launch_bounds__(kMgSmallBlock) void k_mg_small(MgSmall m, const State* st) {
+__global__ __launch_bounds__(kMgLdsBlock) void k_mg_lds(MgLds m, const State* st) {
     if (st->done) return;
-    __shared__ double xs[2][kMgCoarseMax];
+    __shared__ double sb[kMgLdsNodes], sxa[kMgLdsNodes], sxb[kMgLdsNodes];
+    __shared__ uint8_t sty[kMgLdsNodes];
     const int64_t t0 = threadIdx.x, T = blockDim.x;
     const int last = m.levels - 1;
-    for (int l = m.l0; l < last; ++l) {
-        mg_jacobi(m.lv[l], m.xb[l], m.xa[l], m.b[l], 1, t0, T);
-        __syncthreads();
-        mg_jacobi(m.lv[l], m.xa[l], m.xb[l], m.b[l], 0, t0, T);
-        __syncthreads();
-        mg_resid(m.lv[l], m.xb[l], m.b[l], m.t[l], t0, T);
-        __syncthreads();
-        mg_restrict(m.lv[l], m.lv[l + 1], m.t[l], m.bw[l + 1], m.sr[l], m.sz[l], t0, T);
-        __syncthreads();
+    auto lv = [&](int l) {
+        Lv L = m.lv[l];
+        L.type = sty + m.off[l];
+        return L;
+    };
+    for (int l = m.l0; l <= last; ++l) {
+        const int64_t nn = (int64_t)m.lv[l].nr * m.lv[l].nz;
+        for (int64_t n = t0; n < nn; n += T) sty[m.off[l] + n] = m.lv[l].type[n];
     }
-    const Lv& C = m.lv[last];
-    if ((int64_t)C.nr * C.nz <= kMgCoarseMax) {
-        mg_coarse(C, m.b[last], m.xb[last], xs);
-    } else {
-        mg_jacobi(C, m.xb[last], m.xa[last], m.b[last], 1, t0, T);
-        __syncthreads();
-        mg_jacobi(C, m.xa[last], m.xb[last], m.b[last], 0, t0, T);
-        __syncthreads();
-        mg_jacobi(C, m.xb[last], m.xa[last], m.b[last], 0, t0, T);
-        __syncthreads();
-        mg_jacobi(C, m.xa[last], m.xb[last], m.b[last], 0, t0, T);
+    {
+        const int64_t nn = (int64_t)m.lv[m.l0].nr * m.lv[m.l0].nz;
+        for (int64_t n = t0; n < nn; n += T) sb[n] = m.lv[m.l0].type[n] == kFree ? m.b[n] : 0.0;
     }
     __syncthreads();
-    for (int l = last - 1; l >= m.l0; --l) {
-        mg_prolong(m.lv[l], m.lv[l + 1], m.xb[l + 1], m.xb[l], m.sr[l], m.sz[l], t0, T);
+    for (int l = m.l0; l < last; ++l) {
+        const Lv F = lv(l), Cl = lv(l + 1);
+        double *b = sb + m.off[l], *xa = sxa + m.off[l], *xb = sxb + m.off[l];
+        mg_jacobi(F, xb, xa, b, 1, t0, T);
         __syncthreads();
-        mg_jacobi(m.lv[l], m.xb[l], m.xa[l], m.b[l], 0, t0, T);
+        mg_jacobi(F, xa, xb, b, 0, t0, T);
         __syncthreads();
-        mg_jacobi(m.lv[l], m.xa[l], m.xb[l], m.b[l], 0, t0, T);
+        mg_resid(F, xb, b, xa, t0, T);
+        __syncthreads();
+        mg_restrict(F, Cl, xa, sb + m.off[l + 1], m.sr[l], m.sz[l], t0, T);
         __syncthreads();
     }
+    {
+        const Lv C = lv(last);
+        double *b = sb + m.off[last], *xa = sxa + m.off[last], *xb = sxb + m.off[last];
+        if (m.inv) {
+            mg_direct(C, m.inv, b, xb, t0, T);
+            __syncthreads();
+        } else {
+            const int sweeps = (int64_t)C.nr * C.nz <= kMgCoarseMax ? kMgCoarseSweeps : 4;  // even: the result in x_b
+            for (int k = 0; k < sweeps; k += 2) {
+                mg_jacobi(C, xb, xa, b, k == 0, t0, T);
+                __syncthreads();
+                mg_jacobi(C, xa, xb, b, 0, t0, T);
+                __syncthreads();
+            }
+        }
+    }
+    for (int l = last - 1; l >= m.l0; --l) {
+        const Lv F = lv(l), Cl = lv(l + 1);
+        double *b = sb + m.off[l], *xa = sxa + m.off[l], *xb = sxb + m.off[l];
+        mg_prolong(F, Cl, sxb + m.off[l + 1], xb, m.sr[l], m.sz[l], t0, T);
+        __syncthreads();
+        mg_jacobi(F, xb, xa, b, 0, t0, T);
+        __syncthreads();
+        mg_jacobi(F, xa, xb, b, 0, t0, T);
+        __syncthreads();
+    }
+    const int64_t nn = (int64_t)m.lv[m.l0].nr * m.lv[m.l0].nz;
+    for (int64_t n = t0; n < nn; n += T)
+        if (sty[n] == kFree) m.x[n] = sxb[n];
 }
 
 __global__ void k_field(Geo g, const double* phi, double h, double* E) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= (int64_t)g.nr * g.nz) return;
-    const int i = (int)(n % g.nr), k = (int)(n / g.nr);
+    int i, k;
+    node_ik(n, g.nr, i, k);
     double er = 0.0, ez;
     if (i > 0 && i < g.nr - 1) er = -(phi[n + 1] - phi[n - 1]) / (2.0 * h);
     if (k == 0) ez = -(phi[n + g.nr] - phi[n]) / h;
@@ -1547,6 +1709,7 @@ MgDims mg_dims(int nr, int nz) {
     d.nz[0] = nz;
     d.fr[0] = d.fa[0] = 1.0;
     for (int l = 0; l + 1 < kMgMaxLevels; ++l) {
+        if ((int64_t)d.nr[l] * d.nz[l] <= kMgDirectMax) break;  // solved directly
         const bool hr = (d.nr[l] - 1) % 2 == 0 && d.nr[l] - 1 >= 4;
         const bool hz = (d.nz[l] - 1) % 2 == 0 && d.nz[l] - 1 >= 4;
         if (!hr && !hz) break;
@@ -1598,7 +1761,8 @@ struct Work {
     // multigrid levels: types (level 0: the node types), two iterates, the
     // right-hand side (level 0: the CG residual) and the residual
     uint8_t* mtype[kMgMaxLevels] = {};
-    double *mxa[kMgMaxLevels] = {}, *mxb[kMgMaxLevels] = {}, *mb[kMgMaxLevels] = {}, *mt[kMgMaxLevels] = {};
+    double *mxa[kMgMaxLevels] = {}, *mxb[kMgMaxLevels] = {}, *mb[kMgMaxLevels] = {};
+    double* minv = nullptr;  // inverse of the coarsest operator (kMgDirectMax^2)
 };
 
 size_t layout(const pic_rz_config* c, const int64_t cap[3], char* base, Work* w) {
@@ -1663,8 +1827,8 @@ size_t layout(const pic_rz_config* c, const int64_t cap[3], char* base, Work* w)
         }
         t.mxa[l] = (double*)take(m * 8);
         t.mxb[l] = l == 0 ? t.z : (double*)take(m * 8);
-        t.mt[l] = (double*)take(m * 8);
     }
+    t.minv = (double*)take((size_t)kMgDirectMax * kMgDirectMax * 8);
     if (w) *w = t;
     return off + 256;
 }
@@ -1712,6 +1876,7 @@ struct pic_rz_ctx {
     int64_t step = 0;
     int last_iters = 0;
     double sig_max[3] = {0.0, 0.0, 0.0};  // bounds of the class cross sections, from the tables
+    const double* mg_inv = nullptr;        // inverse of the coarsest multigrid operator (w.minv), or null
     // two PCG iterations of the step solve (phi = buf.phi) as one graph
     hipStream_t cap_stream = nullptr;
     hipGraph_t pcg_graph = nullptr;
@@ -1777,26 +1942,29 @@ void vcycle(pic_rz_ctx* c, int l, const double* b, double* xa, double* xb) {
     const Lv L = level(c, l);
     const unsigned G = mg_grid(L);
     const State* st = c->st;
-    if ((int64_t)L.nr * L.nz <= kMgSmallNodes && l < c->mg.levels - 1) {
-        MgSmall m{};
+    int64_t below = 0;  // nodes of the levels from l down
+    for (int k = l; k < c->mg.levels; ++k) below += (int64_t)c->mg.nr[k] * c->mg.nz[k];
+    if (below <= kMgLdsNodes && l < c->mg.levels - 1) {
+        MgLds m{};
         m.l0 = l;
         m.levels = c->mg.levels;
+        int off = 0;
         for (int k = l; k < c->mg.levels; ++k) {
             m.lv[k] = level(c, k);
-            m.b[k] = k == l ? b : c->w.mb[k];
-            m.bw[k] = k == l ? nullptr : c->w.mb[k];
-            m.xa[k] = k == l ? xa : c->w.mxa[k];
-            m.xb[k] = k == l ? xb : c->w.mxb[k];
-            m.t[k] = c->w.mt[k];
+            m.off[k] = off;
+            off += c->mg.nr[k] * c->mg.nz[k];
             m.sr[k] = c->mg.sr[k];
             m.sz[k] = c->mg.sz[k];
         }
-        hipLaunchKernelGGL(k_mg_small, dim3(1), dim3(kMgSmallBlock), 0, c->stream, m, st);
+        m.b = b;
+        m.x = xb;
+        m.inv = c->mg_inv;
+        hipLaunchKernelGGL(k_mg_lds, dim3(1), dim3(kMgLdsBlock), 0, c->stream, m, st);
         return;
     }
     if (l == c->mg.levels - 1) {
         if ((int64_t)L.nr * L.nz <= kMgCoarseMax) {
-            hipLaunchKernelGGL(k_mg_coarse, dim3(1), dim3(kBlock), 0, c->stream, L, b, xb, st);
+            hipLaunchKernelGGL(k_mg_coarse, dim3(1), dim3(kBlock), 0, c->stream, L, b, xb, c->mg_inv, st);
         } else {
             hipLaunchKernelGGL(k_mg_jacobi, dim3(G), dim3(kBlock), 0, c->stream, L, (const double*)xb, xa, b, 1, st);
             hipLaunchKernelGGL(k_mg_jacobi, dim3(G), dim3(kBlock), 0, c->stream, L, (const double*)xa, xb, b, 0, st);
@@ -1807,16 +1975,89 @@ void vcycle(pic_rz_ctx* c, int l, const double* b, double* xa, double* xb) {
     }
     const Lv Cl = level(c, l + 1);
     const int sr = c->mg.sr[l], sz = c->mg.sz[l];
-    hipLaunchKernelGGL(k_mg_jacobi, dim3(G), dim3(kBlock), 0, c->stream, L, (const double*)xb, xa, b, 1, st);
-    hipLaunchKernelGGL(k_mg_jacobi, dim3(G), dim3(kBlock), 0, c->stream, L, (const double*)xa, xb, b, 0, st);
-    hipLaunchKernelGGL(k_mg_resid, dim3(G), dim3(kBlock), 0, c->stream, L, (const double*)xb, b, c->w.mt[l], st);
-    hipLaunchKernelGGL(k_mg_restrict, dim3(mg_grid(Cl)), dim3(kBlock), 0, c->stream, L, Cl,
-                       (const double*)c->w.mt[l], c->w.mb[l + 1], sr, sz, st);
+    // two sweeps from zero, the residual restricted, the coarse correction,
+    // two sweeps (the first with the correction formed on the fly)
+    hipLaunchKernelGGL(k_mg_smooth2, dim3(G), dim3(kBlock), 0, c->stream, L, b, xb, st);
+    hipLaunchKernelGGL(k_mg_resid_restrict, dim3(mg_grid(Cl)), dim3(kBlock), 0, c->stream, L, Cl,
+                       (const double*)xb, b, c->w.mb[l + 1], sr, sz, st);
     vcycle(c, l + 1, c->w.mb[l + 1], c->w.mxa[l + 1], c->w.mxb[l + 1]);
-    hipLaunchKernelGGL(k_mg_prolong, dim3(G), dim3(kBlock), 0, c->stream, L, Cl, (const double*)c->w.mxb[l + 1], xb,
-                       sr, sz, st);
-    hipLaunchKernelGGL(k_mg_jacobi, dim3(G), dim3(kBlock), 0, c->stream, L, (const double*)xb, xa, b, 0, st);
+    hipLaunchKernelGGL(k_mg_prolong_smooth, dim3(G), dim3(kBlock), 0, c->stream, L, Cl,
+                       (const double*)c->w.mxb[l + 1], (const double*)xb, xa, b, sr, sz, st);
     hipLaunchKernelGGL(k_mg_jacobi, dim3(G), dim3(kBlock), 0, c->stream, L, (const double*)xa, xb, b, 0, st);
+}
+
+// The inverse of the coarsest multigrid operator, when that level has at most
+// kMgDirectMax nodes: the operator of lv_apply over the free nodes (held ones
+// at zero), inverted on the host by Gauss-Jordan elimination with partial
+// pivoting, stored nc x nc with zero rows and columns at held nodes.
+pic_status mg_inverse(pic_rz_ctx* c) {
+    c->mg_inv = nullptr;
+    const int l = c->mg.levels - 1;
+    const int nr = c->mg.nr[l], nz = c->mg.nz[l], nc = nr * nz;
+    if (nc > kMgDirectMax) return PIC_OK;
+    std::vector<uint8_t> ty((size_t)nc);
+    const uint8_t* dty = l == 0 ? c->buf.node_type : c->w.mtype[l];
+    pic_status s = hip_ok(c, hipMemcpyAsync(ty.data(), dty, (size_t)nc, hipMemcpyDeviceToHost, c->stream), "copy");
+    if (s == PIC_OK) s = hip_ok(c, hipStreamSynchronize(c->stream), "sync");
+    if (s != PIC_OK) return s;
+    std::vector<int> fr;  // free nodes
+    std::vector<int> at((size_t)nc, -1);
+    for (int n = 0; n < nc; ++n)
+        if (ty[(size_t)n] == kFree) {
+            at[(size_t)n] = (int)fr.size();
+            fr.push_back(n);
+        }
+    const int nf = (int)fr.size();
+    std::vector<double> a((size_t)nf * nf, 0.0), v((size_t)nf * nf, 0.0);
+    for (int r = 0; r < nf; ++r) {
+        const int n = fr[(size_t)r], i = n % nr, k = n / nr;
+        const double cin = i > 0 ? c->mg.fr[l] * 2.0 * (i - 0.5) : 0.0;
+        const double cout = i < nr - 1 ? c->mg.fr[l] * 2.0 * (i + 0.5) : 0.0;
+        const double hi = std::min(i + 0.5, nr - 1.0), lo = std::max(i - 0.5, 0.0);
+        const double cax = c->mg.fa[l] * (hi * hi - lo * lo);
+        a[(size_t)r * nf + r] = cin + cout + 2.0 * cax;
+        auto off = [&](int m, double cf) {
+            if (cf != 0.0 && at[(size_t)m] >= 0) a[(size_t)r * nf + at[(size_t)m]] -= cf;
+        };
+        if (i > 0) off(n - 1, cin);
+        if (i < nr - 1) off(n + 1, cout);
+        if (k > 0) off(n - nr, cax);
+        if (k < nz - 1) off(n + nr, cax);
+        v[(size_t)r * nf + r] = 1.0;
+    }
+    for (int col = 0; col < nf; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < nf; ++r)
+            if (std::fabs(a[(size_t)r * nf + col]) > std::fabs(a[(size_t)piv * nf + col])) piv = r;
+        if (!(std::fabs(a[(size_t)piv * nf + col]) > 0.0))
+            return fail(c, PIC_E_INVALID_ARG, "the coarsest multigrid operator is singular");
+        if (piv != col)
+            for (int j = 0; j < nf; ++j) {
+                std::swap(a[(size_t)piv * nf + j], a[(size_t)col * nf + j]);
+                std::swap(v[(size_t)piv * nf + j], v[(size_t)col * nf + j]);
+            }
+        const double d = a[(size_t)col * nf + col];
+        for (int j = 0; j < nf; ++j) {
+            a[(size_t)col * nf + j] /= d;
+            v[(size_t)col * nf + j] /= d;
+        }
+        for (int r = 0; r < nf; ++r) {
+            if (r == col) continue;
+            const double f = a[(size_t)r * nf + col];
+            if (f == 0.0) continue;
+            for (int j = 0; j < nf; ++j) {
+                a[(size_t)r * nf + j] -= f * a[(size_t)col * nf + j];
+                v[(size_t)r * nf + j] -= f * v[(size_t)col * nf + j];
+            }
+        }
+    }
+    std::vector<double> inv((size_t)nc * nc, 0.0);
+    for (int r = 0; r < nf; ++r)
+        for (int q = 0; q < nf; ++q) inv[(size_t)fr[(size_t)r] * nc + fr[(size_t)q]] = v[(size_t)r * nf + q];
+    s = hip_ok(c, hipMemcpyAsync(c->w.minv, inv.data(), inv.size() * 8, hipMemcpyHostToDevice, c->stream), "copy");
+    if (s == PIC_OK) s = hip_ok(c, hipStreamSynchronize(c->stream), "sync");
+    if (s == PIC_OK) c->mg_inv = c->w.minv;
+    return s;
 }
 
 // Multigrid-preconditioned CG from the current phi (held nodes set to 0 /
@@ -2184,10 +2425,10 @@ pic_status pic_rz_init(const pic_rz_config* cfg, const pic_rz_buffers* bufs, voi
             }
             if (s == PIC_OK) s = hip_ok(c, hipMemsetAsync(c->w.mxa[l], 0, m * 8, c->stream), "zero");
             if (s == PIC_OK) s = hip_ok(c, hipMemsetAsync(c->w.mxb[l], 0, m * 8, c->stream), "zero");
-            if (s == PIC_OK) s = hip_ok(c, hipMemsetAsync(c->w.mt[l], 0, m * 8, c->stream), "zero");
         }
         if (s == PIC_OK) s = hip_ok(c, hipMemsetAsync(c->r, 0, nn * 8, c->stream), "zero");
         if (s == PIC_OK) s = hip_ok(c, hipMemsetAsync(c->p, 0, nn * 8, c->stream), "zero");
+        if (s == PIC_OK) s = mg_inverse(c);
     }
     int it = 0;
     if (s == PIC_OK) s = cg(c, bufs->phi1, 1.0, false, cfg->laplace_rtol, 1000000, &it);
