@@ -470,29 +470,67 @@ __global__ __launch_bounds__(kBlock) void k_mg_smooth2(Lv L, const double* b, do
     }
 }
 
-// b_c = R (b - A x): the residual formed at each fine node the restriction reads
+// The fused kernels read every value a node needs up front (indices clamped
+// into the grid, the ones outside it marked not free), so the loads are in
+// flight together; the arithmetic, in the same order, is that of lv_apply,
+// mg_restrict and mg_prolong. SR, SZ: 2 where the dimension is halved.
+
+// the stencil of lv_apply at column i from a patch: f[c], x[c] the node,
+// f/x[w], [e] its radial and [s], [nn] its axial neighbours (f: free)
+__device__ inline double patch_apply(const Lv& L, int i, const bool* f, const double* x, int c, int w, int e, int s,
+                                     int nn, double& diag) {
+    const double cin = i > 0 ? L.fr * 2.0 * (i - 0.5) : 0.0;
+    const double cout = i < L.nr - 1 ? L.fr * 2.0 * (i + 0.5) : 0.0;
+    const double hi = fmin(i + 0.5, L.nr - 1.0), lo = fmax(i - 0.5, 0.0);
+    const double cax = L.fa * (hi * hi - lo * lo);
+    double a = 0.0;
+    if (cin != 0.0 && f[w]) a -= cin * x[w];
+    if (cout != 0.0 && f[e]) a -= cout * x[e];
+    if (f[s]) a -= cax * x[s];
+    if (f[nn]) a -= cax * x[nn];
+    diag = cin + cout + 2.0 * cax;
+    return a + diag * x[c];
+}
+
+// b_c = R (b - A x): the residual formed at each fine node the restriction
+// reads, from the patch of fine nodes within one node of them
+template <int SR, int SZ>
 __global__ __launch_bounds__(kBlock) void k_mg_resid_restrict(Lv F, Lv Cl, const double* x, const double* b,
-                                                               double* bc, int sr, int sz, const State* st) {
+                                                               double* bc, const State* st) {
     if (st->done) return;
+    constexpr int RI = SR - 1, RK = SZ - 1, PW = 2 * RI + 3, PH = 2 * RK + 3;
     const int64_t nn = (int64_t)Cl.nr * Cl.nz;
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (int64_t)gridDim.x * blockDim.x) {
         if (Cl.type[n] != kFree) continue;
         int I, K;
         node_ik(n, Cl.nr, I, K);
-        const int i0 = sr * I, k0 = sz * K;
+        const int i0 = SR * I, k0 = SZ * K;
+        bool f[PH * PW];
+        double xp[PH * PW], bp[PH * PW];
+#pragma unroll
+        for (int pk = 0; pk < PH; ++pk)
+#pragma unroll
+            for (int pi = 0; pi < PW; ++pi) {
+                const int i = i0 + pi - RI - 1, k = k0 + pk - RK - 1;
+                const bool in = i >= 0 && i < F.nr && k >= 0 && k < F.nz;
+                const int64_t m = in ? (int64_t)k * F.nr + i : 0;
+                f[pk * PW + pi] = in && F.type[m] == kFree;
+                xp[pk * PW + pi] = x[m];
+                const bool inner = pi >= 1 && pi <= PW - 2 && pk >= 1 && pk <= PH - 2;
+                bp[pk * PW + pi] = inner ? b[m] : 0.0;
+            }
         double s = 0.0;
-        for (int dk = -(sz - 1); dk <= sz - 1; ++dk) {
-            const int k = k0 + dk;
-            if (k < 0 || k >= F.nz) continue;
+#pragma unroll
+        for (int dk = -RK; dk <= RK; ++dk) {
             const double wk = dk == 0 ? 1.0 : 0.5;
-            for (int di = -(sr - 1); di <= sr - 1; ++di) {
-                const int i = i0 + di;
-                if (i < 0 || i >= F.nr) continue;
+#pragma unroll
+            for (int di = -RI; di <= RI; ++di) {
                 const double wi = di == 0 ? 1.0 : 0.5;
-                const int64_t m = (int64_t)k * F.nr + i;
-                if (F.type[m] != kFree) continue;
+                const int c = (dk + RK + 1) * PW + di + RI + 1;
+                if (!f[c]) continue;
                 double d;
-                const double t = b[m] - lv_apply(F, x, m, i, k, d);
+                const double ax = patch_apply(F, i0 + di, f, xp, c, c - 1, c + 1, c - PW, c + PW, d);
+                const double t = bp[c] - ax;
                 s += wi * wk * t;
             }
         }
@@ -500,46 +538,54 @@ __global__ __launch_bounds__(kBlock) void k_mg_resid_restrict(Lv F, Lv Cl, const
     }
 }
 
-// the bilinear correction P x_c at fine node n (free)
-__device__ inline double mg_corr(const Lv& Cl, const double* xc, int sr, int sz, int i, int k) {
-    int I0 = i, I1 = i, K0 = k, K1 = k;
-    if (sr == 2) {
-        I0 = i >> 1;
-        I1 = (i + 1) >> 1;
-    }
-    if (sz == 2) {
-        K0 = k >> 1;
-        K1 = (k + 1) >> 1;
-    }
+// the bilinear correction P x_c at fine node (i, k) (free); SR, SZ as above
+template <int SR, int SZ>
+__device__ inline double mg_corr(const Lv& Cl, const double* xc, int i, int k) {
+    const int I0 = SR == 2 ? i >> 1 : i, I1 = SR == 2 ? (i + 1) >> 1 : i;
+    const int K0 = SZ == 2 ? k >> 1 : k, K1 = SZ == 2 ? (k + 1) >> 1 : k;
     const double wi = I0 == I1 ? 1.0 : 0.5, wk = K0 == K1 ? 1.0 : 0.5;
-    auto at = [&](int I, int K) {
-        const int64_t m = (int64_t)K * Cl.nr + I;
-        return Cl.type[m] == kFree ? xc[m] : 0.0;
-    };
-    double v = at(I0, K0);
-    if (I1 != I0) v += at(I1, K0);
+    const int64_t m00 = (int64_t)K0 * Cl.nr + I0, m10 = (int64_t)K0 * Cl.nr + I1;
+    const int64_t m01 = (int64_t)K1 * Cl.nr + I0, m11 = (int64_t)K1 * Cl.nr + I1;
+    const double a00 = Cl.type[m00] == kFree ? xc[m00] : 0.0;
+    const double a10 = Cl.type[m10] == kFree ? xc[m10] : 0.0;
+    const double a01 = Cl.type[m01] == kFree ? xc[m01] : 0.0;
+    const double a11 = Cl.type[m11] == kFree ? xc[m11] : 0.0;
+    double v = a00;
+    if (I1 != I0) v += a10;
     if (K1 != K0) {
-        v += at(I0, K1);
-        if (I1 != I0) v += at(I1, K1);
+        v += a01;
+        if (I1 != I0) v += a11;
     }
     return wi * wk * v;
 }
 
 // y = one sweep from x + P x_c (the corrected value formed at the node and
 // its neighbours; x itself is not written)
+template <int SR, int SZ>
 __global__ __launch_bounds__(kBlock) void k_mg_prolong_smooth(Lv F, Lv Cl, const double* xc, const double* x,
-                                                               double* y, const double* b, int sr, int sz,
-                                                               const State* st) {
+                                                               double* y, const double* b, const State* st) {
     if (st->done) return;
     const int64_t nn = (int64_t)F.nr * F.nz;
     for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (int64_t)gridDim.x * blockDim.x) {
         if (F.type[n] != kFree) continue;
         int i, k;
         node_ik(n, F.nr, i, k);
-        auto xv = [&](int64_t m, int im, int km) { return x[m] + mg_corr(Cl, xc, sr, sz, im, km); };
+        // the node (0) and its neighbours west, east, south, north (1-4), clamped into the grid
+        const int di[5] = {0, -1, 1, 0, 0}, dk[5] = {0, 0, 0, -1, 1};
+        bool f[5];
+        double v[5];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            const int iq = i + di[q], kq = k + dk[q];
+            const bool in = iq >= 0 && iq < F.nr && kq >= 0 && kq < F.nz;
+            const int ic = in ? iq : i, kc = in ? kq : k;
+            const int64_t m = (int64_t)kc * F.nr + ic;
+            f[q] = in && F.type[m] == kFree;
+            v[q] = x[m] + mg_corr<SR, SZ>(Cl, xc, ic, kc);
+        }
         double d;
-        const double ax = lv_apply_f(F, n, i, k, d, xv);
-        y[n] = xv(n, i, k) + kMgOmega * (b[n] - ax) / d;
+        const double ax = patch_apply(F, i, f, v, 0, 1, 2, 3, 4, d);
+        y[n] = v[0] + kMgOmega * (b[n] - ax) / d;
     }
 }
 
@@ -1079,8 +1125,17 @@ __global__ __launch_bounds__(kBlock) void k_rank(CollArgs a) {
         if (j == b) a.big[atomicAdd(&a.st->nbig, 1u)] = (uint32_t)key;
         return;
     }
-    int64_t rank = 0;
-    for (int64_t k = 0; k < m; ++k) rank += a.segid[b + k] < myid ? 1 : 0;
+    // eight loads in flight at a time
+    int rank = 0;
+    int64_t k = 0;
+    for (; k + 8 <= m; k += 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = a.segid[b + k + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) rank += v[u] < myid ? 1 : 0;
+    }
+    for (; k < m; ++k) rank += a.segid[b + k] < myid ? 1 : 0;
     a.sorted[b + rank] = p;
     a.crank[a.off[s] + p] = (uint32_t)rank;
 }
@@ -1977,12 +2032,17 @@ void vcycle(pic_rz_ctx* c, int l, const double* b, double* xa, double* xb) {
     const int sr = c->mg.sr[l], sz = c->mg.sz[l];
     // two sweeps from zero, the residual restricted, the coarse correction,
     // two sweeps (the first with the correction formed on the fly)
+    // (sr, sz) is (2, 2), (2, 1) or (1, 2): a level is made only where a dimension halves
+    auto resid_restrict = sr == 2 ? (sz == 2 ? k_mg_resid_restrict<2, 2> : k_mg_resid_restrict<2, 1>)
+                                  : k_mg_resid_restrict<1, 2>;
+    auto prolong_smooth = sr == 2 ? (sz == 2 ? k_mg_prolong_smooth<2, 2> : k_mg_prolong_smooth<2, 1>)
+                                  : k_mg_prolong_smooth<1, 2>;
     hipLaunchKernelGGL(k_mg_smooth2, dim3(G), dim3(kBlock), 0, c->stream, L, b, xb, st);
-    hipLaunchKernelGGL(k_mg_resid_restrict, dim3(mg_grid(Cl)), dim3(kBlock), 0, c->stream, L, Cl,
-                       (const double*)xb, b, c->w.mb[l + 1], sr, sz, st);
+    hipLaunchKernelGGL(resid_restrict, dim3(mg_grid(Cl)), dim3(kBlock), 0, c->stream, L, Cl, (const double*)xb, b,
+                       c->w.mb[l + 1], st);
     vcycle(c, l + 1, c->w.mb[l + 1], c->w.mxa[l + 1], c->w.mxb[l + 1]);
-    hipLaunchKernelGGL(k_mg_prolong_smooth, dim3(G), dim3(kBlock), 0, c->stream, L, Cl,
-                       (const double*)c->w.mxb[l + 1], (const double*)xb, xa, b, sr, sz, st);
+    hipLaunchKernelGGL(prolong_smooth, dim3(G), dim3(kBlock), 0, c->stream, L, Cl, (const double*)c->w.mxb[l + 1],
+                       (const double*)xb, xa, b, st);
     hipLaunchKernelGGL(k_mg_jacobi, dim3(G), dim3(kBlock), 0, c->stream, L, (const double*)xa, xb, b, 0, st);
 }
 

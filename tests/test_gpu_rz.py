@@ -332,6 +332,34 @@ def test_rz_multigrid_levels_solve():
     assert np.abs(phi - o.phi).max() <= 1e-9 * np.abs(o.phi).max()
 
 
+@pytest.mark.parametrize("shape", [(8, 1025, 4e-9, 40e-9), (1025, 8, 4e-9, 8e-9)])
+def test_rz_multigrid_one_dimension_halved(shape):
+    """Grids where only one dimension halves (7 x 1024 and 1024 x 7 cells):
+    the multigrid levels above the LDS-resident ones coarsen along z only or
+    along r only; the unit-anode potential and a solve with charge as the
+    oracle's direct solution."""
+    nr, nz, tip_r, tip_h = shape
+    print(f"case: rz multigrid one dimension halved nr={nr} nz={nz}", flush=True)
+    geom = dict(GEOM, nr=nr, nz=nz, tip_r=tip_r, tip_h=tip_h)
+    o = RZ(geom["nr"], geom["nz"], geom["h"], geom["tip_r"], geom["tip_h"], geom["apex_field"], geom["dt"],
+           geom["m_ion"])
+    load = _load(o, np.random.default_rng(43), (8000, 4000, 0))
+    nid = 0
+    for s in range(3):
+        m = len(load[s]["r"])
+        o.load(s, load[s], np.arange(nid, nid + m))
+        nid += m
+    g = rz.RZSimulation(**geom, load=load, laplace_rtol=1e-13, step_rtol=1e-12)
+    assert np.abs(g.grid("phi1") - o.phi1).max() <= 1e-10
+    g.step(1, rz.PIC_RZ_DEPOSIT)
+    o.deposit()
+    info = g.solve(1e-12, 5000)
+    o.solve()
+    assert info["converged"], info
+    phi = g.grid("phi")
+    assert np.abs(phi - o.phi).max() <= 1e-9 * np.abs(o.phi).max()
+
+
 def _load_cu2(seed, n=(3000, 1500, 6000)):
     o0 = RZ(GEOM["nr"], GEOM["nz"], GEOM["h"], GEOM["tip_r"], GEOM["tip_h"], GEOM["apex_field"], GEOM["dt"],
             GEOM["m_ion"])
