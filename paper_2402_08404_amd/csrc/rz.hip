@@ -321,18 +321,25 @@ struct Lv {
 
 // sum_j c (x_n - x_m) over the neighbours (held ones at zero) and the
 // diagonal, at node n = (i, k); xv(m, i, k) gives the value of node m = (i, k)
+// (the neighbours' types and values are read unconditionally, at indices
+// clamped into the grid, so that the loads are in flight together)
 template <class X>
 __device__ inline double lv_apply_f(const Lv& L, int64_t n, int i, int k, double& diag, X xv) {
     const double cin = i > 0 ? L.fr * 2.0 * (i - 0.5) : 0.0;
     const double cout = i < L.nr - 1 ? L.fr * 2.0 * (i + 0.5) : 0.0;
     const double hi = fmin(i + 0.5, L.nr - 1.0), lo = fmax(i - 0.5, 0.0);
     const double cax = L.fa * (hi * hi - lo * lo);
+    const bool iw = i > 0, ie = i < L.nr - 1, is = k > 0, in = k < L.nz - 1;
+    const int64_t mw = iw ? n - 1 : n, me = ie ? n + 1 : n, ms = is ? n - L.nr : n, mn = in ? n + L.nr : n;
+    const uint8_t tw = L.type[mw], te = L.type[me], ts = L.type[ms], tn = L.type[mn];
     const double xn = xv(n, i, k);
+    const double xw = xv(mw, iw ? i - 1 : i, k), xe = xv(me, ie ? i + 1 : i, k);
+    const double xs = xv(ms, i, is ? k - 1 : k), xq = xv(mn, i, in ? k + 1 : k);
     double s = 0.0;
-    if (cin != 0.0 && L.type[n - 1] == kFree) s -= cin * xv(n - 1, i - 1, k);
-    if (cout != 0.0 && L.type[n + 1] == kFree) s -= cout * xv(n + 1, i + 1, k);
-    if (k > 0 && L.type[n - L.nr] == kFree) s -= cax * xv(n - L.nr, i, k - 1);
-    if (k < L.nz - 1 && L.type[n + L.nr] == kFree) s -= cax * xv(n + L.nr, i, k + 1);
+    if ((cin != 0.0) & (tw == kFree)) s -= cin * xw;
+    if ((cout != 0.0) & (te == kFree)) s -= cout * xe;
+    if (is & (ts == kFree)) s -= cax * xs;
+    if (in & (tn == kFree)) s -= cax * xq;
     diag = cin + cout + 2.0 * cax;
     return s + diag * xn;
 }
@@ -514,7 +521,8 @@ __global__ __launch_bounds__(kBlock) void k_mg_resid_restrict(Lv F, Lv Cl, const
                 const int i = i0 + pi - RI - 1, k = k0 + pk - RK - 1;
                 const bool in = i >= 0 && i < F.nr && k >= 0 && k < F.nz;
                 const int64_t m = in ? (int64_t)k * F.nr + i : 0;
-                f[pk * PW + pi] = in && F.type[m] == kFree;
+                const uint8_t t = F.type[m];  // loaded whether or not inside: no branch between the loads
+                f[pk * PW + pi] = in & (t == kFree);
                 xp[pk * PW + pi] = x[m];
                 const bool inner = pi >= 1 && pi <= PW - 2 && pk >= 1 && pk <= PH - 2;
                 bp[pk * PW + pi] = inner ? b[m] : 0.0;
@@ -580,7 +588,8 @@ __global__ __launch_bounds__(kBlock) void k_mg_prolong_smooth(Lv F, Lv Cl, const
             const bool in = iq >= 0 && iq < F.nr && kq >= 0 && kq < F.nz;
             const int ic = in ? iq : i, kc = in ? kq : k;
             const int64_t m = (int64_t)kc * F.nr + ic;
-            f[q] = in && F.type[m] == kFree;
+            const uint8_t t = F.type[m];
+            f[q] = in & (t == kFree);
             v[q] = x[m] + mg_corr<SR, SZ>(Cl, xc, ic, kc);
         }
         double d;
@@ -597,8 +606,10 @@ __device__ inline void mg_direct(const Lv& C, const double* inv, const double* b
     for (int64_t j = n0; j < nc; j += stride) {
         if (C.type[j] != kFree) continue;
         double s = 0.0;
-        for (int k = 0; k < nc; ++k)
-            if (C.type[k] == kFree) s += inv[j * nc + k] * b[k];
+        for (int k = 0; k < nc; ++k) {
+            const double w = inv[j * nc + k], bk = b[k];  // read unconditionally (b of held nodes is never used)
+            if (C.type[k] == kFree) s += w * bk;
+        }
         x[j] = s;
     }
 }
@@ -655,6 +666,7 @@ struct MgLds {
 __global__ __launch_bounds__(kMgLdsBlock) void k_mg_lds(MgLds m, const State* st) {
     if (st->done) return;
     __shared__ double sb[kMgLdsNodes], sxa[kMgLdsNodes], sxb[kMgLdsNodes];
+    __shared__ double sinv[kMgDirectMax * kMgDirectMax];
     __shared__ uint8_t sty[kMgLdsNodes];
     const int64_t t0 = threadIdx.x, T = blockDim.x;
     const int last = m.levels - 1;
@@ -669,7 +681,14 @@ __global__ __launch_bounds__(kMgLdsBlock) void k_mg_lds(MgLds m, const State* st
     }
     {
         const int64_t nn = (int64_t)m.lv[m.l0].nr * m.lv[m.l0].nz;
-        for (int64_t n = t0; n < nn; n += T) sb[n] = m.lv[m.l0].type[n] == kFree ? m.b[n] : 0.0;
+        for (int64_t n = t0; n < nn; n += T) {
+            const double v = m.b[n];
+            sb[n] = m.lv[m.l0].type[n] == kFree ? v : 0.0;
+        }
+        if (m.inv) {
+            const int64_t nc = (int64_t)m.lv[last].nr * m.lv[last].nz;
+            for (int64_t q = t0; q < nc * nc; q += T) sinv[q] = m.inv[q];
+        }
     }
     __syncthreads();
     for (int l = m.l0; l < last; ++l) {
@@ -688,7 +707,7 @@ __global__ __launch_bounds__(kMgLdsBlock) void k_mg_lds(MgLds m, const State* st
         const Lv C = lv(last);
         double *b = sb + m.off[last], *xa = sxa + m.off[last], *xb = sxb + m.off[last];
         if (m.inv) {
-            mg_direct(C, m.inv, b, xb, t0, T);
+            mg_direct(C, sinv, b, xb, t0, T);
             __syncthreads();
         } else {
             const int sweeps = (int64_t)C.nr * C.nz <= kMgCoarseMax ? kMgCoarseSweeps : 4;  // even: the result in x_b
