@@ -1051,7 +1051,11 @@ __global__ __launch_bounds__(kBlock) void k_cells(CollArgs a, int s) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool in = p < (int64_t)a.st->n[s];
     int32_t c = -1;
-    if (in && a.id[s][p] != kDead) c = cell_index(a.g, a.r[s][p], a.z[s][p]);
+    if (in) {
+        const uint32_t id = a.id[s][p];
+        const double r = a.r[s][p], z = a.z[s][p];  // read with the id, not after it
+        if (id != kDead) c = cell_index(a.g, r, z);
+    }
     const int lane = threadIdx.x & 63;
     const int32_t prev = __shfl_up(c, 1, 64);
     const bool head = lane == 0 || prev != c;
@@ -1134,27 +1138,30 @@ __global__ __launch_bounds__(kBlock) void k_deposit_grouped(CollArgs a, int64_t*
 // in ascending id order; the lanes of a wavefront that share a cell read the
 // same addresses together. Larger cells are listed for k_sort_big.
 __global__ __launch_bounds__(kBlock) void k_rank(CollArgs a) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= (int64_t)a.st->total) return;  // the particles grouped, from the scan of the counts
+    // A cell of at most kRankSmall particles holding j lies within
+    // kRankSmall - 1 places of j: the block's ids and that margin on each
+    // side are staged in LDS once, and the counts read them there.
+    __shared__ uint32_t sid[kBlock + 2 * kRankSmall];
+    const int64_t j0 = (int64_t)blockIdx.x * kBlock, j = j0 + threadIdx.x;
+    const int64_t total = a.st->total;  // the particles grouped, from the scan of the counts
+    const int64_t w0 = j0 - kRankSmall;
+    for (int q = threadIdx.x; q < kBlock + 2 * kRankSmall; q += kBlock) {
+        const int64_t idx = w0 + q;
+        sid[q] = idx >= 0 && idx < total ? a.segid[idx] : 0u;
+    }
+    __syncthreads();
+    if (j >= total) return;
     const int s = j < (int64_t)a.start[a.nc] ? 0 : (j < (int64_t)a.start[2 * a.nc] ? 1 : 2);
-    const uint32_t p = a.seg[j], myid = a.segid[j];
+    const uint32_t p = a.seg[j], myid = sid[j - w0];
     const int64_t key = s * a.nc + a.cellof[a.off[s] + p];
     const int64_t b = a.start[key], m = a.cnt[key];
     if (m > kRankSmall) {
         if (j == b) a.big[atomicAdd(&a.st->nbig, 1u)] = (uint32_t)key;
         return;
     }
-    // eight loads in flight at a time
+    const uint32_t* ids = sid + (b - w0);
     int rank = 0;
-    int64_t k = 0;
-    for (; k + 8 <= m; k += 8) {
-        uint32_t v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = a.segid[b + k + u];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) rank += v[u] < myid ? 1 : 0;
-    }
-    for (; k < m; ++k) rank += a.segid[b + k] < myid ? 1 : 0;
+    for (int k = 0; k < (int)m; ++k) rank += ids[k] < myid ? 1 : 0;
     a.sorted[b + rank] = p;
     a.crank[a.off[s] + p] = (uint32_t)rank;
 }
