@@ -332,12 +332,15 @@ def test_rz_multigrid_levels_solve():
     assert np.abs(phi - o.phi).max() <= 1e-9 * np.abs(o.phi).max()
 
 
-@pytest.mark.parametrize("shape", [(8, 1025, 4e-9, 40e-9), (1025, 8, 4e-9, 8e-9)])
+@pytest.mark.parametrize("shape", [(8, 1025, 4e-9, 40e-9), (1025, 8, 4e-9, 8e-9), (32, 161, 4e-9, 40e-9),
+                                   (5, 12, 2e-9, 10e-9)])
 def test_rz_multigrid_one_dimension_halved(shape):
-    """Grids where only one dimension halves (7 x 1024 and 1024 x 7 cells):
-    the multigrid levels above the LDS-resident ones coarsen along z only or
-    along r only; the unit-anode potential and a solve with charge as the
-    oracle's direct solution."""
+    """Grids where only one dimension halves (7 x 1024, 1024 x 7 and 31 x 160
+    cells): the multigrid levels above the LDS-resident ones coarsen along z
+    only or along r only; on 31 x 160 cells the coarsest level (32 x 6 nodes)
+    is too large for the exact solve and is swept instead; a grid of 60 nodes
+    is its own coarsest level, solved exactly. The unit-anode potential and a
+    solve with charge as the oracle's direct solution."""
     nr, nz, tip_r, tip_h = shape
     print(f"case: rz multigrid one dimension halved nr={nr} nz={nz}", flush=True)
     geom = dict(GEOM, nr=nr, nz=nz, tip_r=tip_r, tip_h=tip_h)
