@@ -308,7 +308,7 @@ def test_rz_collide_dense_cells():
 
 
 def test_rz_multigrid_levels_solve():
-    """A grid whose cell counts halve (32 x 80 cells: five multigrid levels):
+    """A grid whose cell counts halve (32 x 80 cells: four multigrid levels):
     the unit-anode potential and a solve with charge as the oracle's direct
     solution, in a few preconditioned iterations."""
     print("case: rz multigrid levels", flush=True)
