@@ -761,10 +761,14 @@ struct PushArgs {
 
 __global__ __launch_bounds__(kBlock) void k_push(PushArgs a) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= (int64_t)a.st->n[a.sp] || a.id[p] == kDead) return;
-    const Geo& g = a.g;
+    if (p >= (int64_t)a.st->n[a.sp]) return;
+    // the state is read with the id (not after it), so the loads are in flight together
+    const uint32_t id = a.id[p];
     double r = a.r[p], z = a.z[p], vr = a.vr[p], vt = a.vt[p], vz = a.vz[p];
-    const double kq = a.charge ? a.kq * (double)a.charge[p] : a.kq;
+    const double qs = a.charge ? (double)a.charge[p] : 1.0;
+    if (id == kDead) return;
+    const Geo& g = a.g;
+    const double kq = a.charge ? a.kq * qs : a.kq;
     if (kq != 0.0) {
         const int i = clampi((int)floor(r), 0, g.nr - 2), k = clampi((int)floor(z), 0, g.nz - 2);
         const double fr = r - i, fz = z - k;
@@ -817,9 +821,11 @@ __global__ __launch_bounds__(kBlock) void k_deposit(Geo g, const double* r, cons
                                                      const State* st, int sp, int64_t sign0, int64_t* rho, int tail,
                                                      const uint8_t* charge) {
     const int64_t p = (tail ? (int64_t)st->ngrp[sp] : 0) + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= (int64_t)st->n[sp] || id[p] == kDead) return;
-    const int64_t sign = charge ? sign0 * (int64_t)charge[p] : sign0;
+    if (p >= (int64_t)st->n[sp]) return;
+    const uint32_t pid = id[p];
     const double R = r[p], Z = z[p];
+    const int64_t sign = charge ? sign0 * (int64_t)charge[p] : sign0;
+    if (pid == kDead) return;
     const int i = clampi((int)floor(R), 0, g.nr - 2), k = clampi((int)floor(Z), 0, g.nz - 2);
     const int64_t qr = pic::quantize(R - i, 20), qz = pic::quantize(Z - k, 20);
     const int64_t one = 1 << 20;
