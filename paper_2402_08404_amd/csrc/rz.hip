@@ -901,7 +901,11 @@ __global__ void k_check_charge(const uint8_t* q, int64_t n, State* st) {
 // chunks of 4 kScanBlock (each thread a run of four, wavefront shuffles, the
 // wavefront totals in shared memory); the grand total goes to st->total.
 template <typename TO>
-__global__ __launch_bounds__(kScanBlock) void k_scan(const uint32_t* in, TO* out, int64_t m, State* st) {
+__global__ __launch_bounds__(kScanBlock) void k_scan(const uint32_t* in, TO* out, int64_t m, State* st,
+                                                     const unsigned long long* mdev = nullptr, int per = 1) {
+    // mdev: the length is ceil(*mdev / per), at most m (a list whose length
+    // only the device knows)
+    if (mdev) m = std::min<int64_t>(m, (int64_t)((*mdev + per - 1) / per));
     __shared__ unsigned long long wsum[kScanBlock / 64];
     __shared__ unsigned long long carry_s;
     if (threadIdx.x == 0) carry_s = 0;
@@ -946,48 +950,61 @@ __global__ __launch_bounds__(kScanBlock) void k_scan(const uint32_t* in, TO* out
 // total, k_scan_apply the prefix inside every chunk plus the chunk's offset.
 constexpr int kScanChunk = 4 * kScanBlock;
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_sums(const uint32_t* in, int64_t m, uint32_t* sums) {
+// (with mdev: m = min(m, *mdev), the blocks taking the chunks in turn)
+__global__ __launch_bounds__(kScanBlock) void k_scan_sums(const uint32_t* in, int64_t m, uint32_t* sums,
+                                                           const unsigned long long* mdev = nullptr) {
     __shared__ unsigned long long ws[kScanBlock / 64];
-    const int64_t i0 = (int64_t)blockIdx.x * kScanChunk + 4 * (int64_t)threadIdx.x;
-    unsigned long long run = 0;
+    if (mdev) m = std::min<int64_t>(m, (int64_t)*mdev);
+    const int64_t nb = (m + kScanChunk - 1) / kScanChunk;
+    for (int64_t b = blockIdx.x; b < (mdev ? nb : (int64_t)blockIdx.x + 1); b += gridDim.x) {
+        const int64_t i0 = b * kScanChunk + 4 * (int64_t)threadIdx.x;
+        unsigned long long run = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) run += i0 + k < m ? (unsigned long long)in[i0 + k] : 0ull;
-    run = pic::wave_sum(run);
-    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = run;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned long long t = 0;
-        for (int q = 0; q < kScanBlock / 64; ++q) t += ws[q];
-        sums[blockIdx.x] = (uint32_t)t;
+        for (int k = 0; k < 4; ++k) run += i0 + k < m ? (unsigned long long)in[i0 + k] : 0ull;
+        run = pic::wave_sum(run);
+        if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = run;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long t = 0;
+            for (int q = 0; q < kScanBlock / 64; ++q) t += ws[q];
+            sums[b] = (uint32_t)t;
+        }
+        __syncthreads();
     }
 }
 
 __global__ __launch_bounds__(kScanBlock) void k_scan_apply(const uint32_t* in, uint32_t* out, int64_t m,
-                                                            const uint32_t* offs) {
+                                                            const uint32_t* offs,
+                                                            const unsigned long long* mdev = nullptr) {
     __shared__ unsigned long long wsum[kScanBlock / 64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t i0 = (int64_t)blockIdx.x * kScanChunk + 4 * (int64_t)threadIdx.x;
-    unsigned long long v[4], run = 0;
+    if (mdev) m = std::min<int64_t>(m, (int64_t)*mdev);
+    const int64_t nb = (m + kScanChunk - 1) / kScanChunk;
+    for (int64_t b = blockIdx.x; b < (mdev ? nb : (int64_t)blockIdx.x + 1); b += gridDim.x) {
+        const int64_t i0 = b * kScanChunk + 4 * (int64_t)threadIdx.x;
+        unsigned long long v[4], run = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        v[k] = i0 + k < m ? (unsigned long long)in[i0 + k] : 0ull;
-        run += v[k];
-    }
-    unsigned long long x = run;
+        for (int k = 0; k < 4; ++k) {
+            v[k] = i0 + k < m ? (unsigned long long)in[i0 + k] : 0ull;
+            run += v[k];
+        }
+        unsigned long long x = run;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const unsigned long long y = __shfl_up(x, o, 64);
-        if (lane >= o) x += y;
-    }
-    if (lane == 63) wsum[w] = x;
-    __syncthreads();
-    unsigned long long pre = offs[blockIdx.x];
-    for (int q = 0; q < w; ++q) pre += wsum[q];
-    pre += x - run;
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
+        __syncthreads();
+        unsigned long long pre = offs[b];
+        for (int q = 0; q < w; ++q) pre += wsum[q];
+        pre += x - run;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (i0 + k < m) out[i0 + k] = (uint32_t)pre;
-        pre += v[k];
+        for (int k = 0; k < 4; ++k) {
+            if (i0 + k < m) out[i0 + k] = (uint32_t)pre;
+            pre += v[k];
+        }
+        __syncthreads();
     }
 }
 
@@ -1526,23 +1543,21 @@ __global__ __launch_bounds__(1024) void k_prod_sort(CollArgs a) {
     }
 }
 
-// new ions and electrons of every sorted entry, 0 beyond the list
+// new ions and electrons of every sorted entry (grid-stride over the list)
 __global__ __launch_bounds__(kBlock) void k_prod_counts(CollArgs a) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= a.pcap) return;
-    uint32_t ni = 0, ne = 0;
-    if (j < (int64_t)a.st->nprod) {
+    const int64_t n = (int64_t)a.st->nprod;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
         const uint32_t kind = (uint32_t)(a.pkey[j] >> 32);
-        ne = 1;
+        uint32_t ni = 0, ne = 1;
         if (kind == 0) {
             ni = 1;
             ne = a.pflag[a.pslot[j]] == 3 ? 2 : 1;
         } else if (kind == 1) {
             ni = 1;
         }
+        a.pci[j] = ni;
+        a.pce[j] = ne;
     }
-    a.pci[j] = ni;
-    a.pce[j] = ne;
 }
 
 // room for the products' ions and electrons and their ids
@@ -1550,7 +1565,7 @@ __global__ void k_prod_commit(CollArgs a) {
     if (threadIdx.x != 0) return;
     State* st = a.st;
     st->skip = 0;
-    const int64_t L = a.pcap;
+    const int64_t L = (int64_t)st->nprod;
     const unsigned long long TI = L ? (unsigned long long)a.ppi[L - 1] + a.pci[L - 1] : 0ull;
     const unsigned long long TE = L ? (unsigned long long)a.ppe[L - 1] + a.pce[L - 1] : 0ull;
     if (TI + TE == 0) return;
@@ -1572,9 +1587,8 @@ __global__ void k_prod_commit(CollArgs a) {
     st->next_id += TI + TE;
 }
 
-__global__ __launch_bounds__(kBlock) void k_prod_place(CollArgs a) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= (int64_t)a.st->nprod || a.st->skip) return;
+// the slots and ids of sorted entry j
+__device__ inline void prod_place_one(const CollArgs& a, int64_t j) {
     const uint32_t kind = (uint32_t)(a.pkey[j] >> 32);
     const int64_t p = a.pslot[j];
     const uint32_t ne = a.pce[j];
@@ -1615,6 +1629,13 @@ __global__ __launch_bounds__(kBlock) void k_prod_place(CollArgs a) {
         a.id[0][se + q] = (uint32_t)(id0 + 1 + q);
     }
     a.id[2][p] = kDead;
+}
+
+__global__ __launch_bounds__(kBlock) void k_prod_place(CollArgs a) {
+    if (a.st->skip) return;
+    const int64_t n = (int64_t)a.st->nprod;
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x)
+        prod_place_one(a, j);
 }
 
 // Reorder of species s by cell, ascending id in a cell (the grouping's
@@ -2297,18 +2318,22 @@ CollArgs coll_args(pic_rz_ctx* c, uint32_t step) {
     return a;
 }
 
-// exclusive prefix of m counts into out, the total into st->total
-void scan_u32(pic_rz_ctx* c, const uint32_t* in, uint32_t* out, int64_t m) {
+// exclusive prefix of m counts into out, the total into st->total; with
+// mdev, of the first min(m, *mdev) counts (a length only the device knows:
+// the blocks of a grid bounded by m take the chunks in turn)
+void scan_u32(pic_rz_ctx* c, const uint32_t* in, uint32_t* out, int64_t m,
+              const unsigned long long* mdev = nullptr) {
     if (m <= 4 * (int64_t)kScanChunk) {
-        hipLaunchKernelGGL(k_scan<uint32_t>, dim3(1), dim3(kScanBlock), 0, c->stream, in, out, m, c->st);
+        hipLaunchKernelGGL(k_scan<uint32_t>, dim3(1), dim3(kScanBlock), 0, c->stream, in, out, m, c->st, mdev, 1);
         return;
     }
     const int64_t nb = (m + kScanChunk - 1) / kScanChunk;
-    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(kScanBlock), 0, c->stream, in, m, c->w.ssum);
+    const unsigned G = (unsigned)(mdev ? std::min<int64_t>(nb, 256) : nb);
+    hipLaunchKernelGGL(k_scan_sums, dim3(G), dim3(kScanBlock), 0, c->stream, in, m, c->w.ssum, mdev);
     hipLaunchKernelGGL(k_scan<uint32_t>, dim3(1), dim3(kScanBlock), 0, c->stream, (const uint32_t*)c->w.ssum,
-                       c->w.spre, nb, c->st);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanBlock), 0, c->stream, in, out, m,
-                       (const uint32_t*)c->w.spre);
+                       c->w.spre, nb, c->st, mdev, kScanChunk);
+    hipLaunchKernelGGL(k_scan_apply, dim3(G), dim3(kScanBlock), 0, c->stream, in, out, m,
+                       (const uint32_t*)c->w.spre, mdev);
 }
 
 // grouping by (species, cell), ascending id within a cell
@@ -2376,11 +2401,15 @@ void collide(pic_rz_ctx* c, uint32_t step) {
     if (a.pcap == 0) return;
     hipLaunchKernelGGL(k_prod_list, dim3(grid_of(a.pcap)), dim3(kBlock), 0, c->stream, a);
     hipLaunchKernelGGL(k_prod_sort, dim3(1), dim3(1024), 0, c->stream, a);
-    hipLaunchKernelGGL(k_prod_counts, dim3(grid_of(a.pcap)), dim3(kBlock), 0, c->stream, a);
-    scan_u32(c, a.pci, a.ppi, a.pcap);
-    scan_u32(c, a.pce, a.ppe, a.pcap);
+    // the kernels after the sort cover the list's entries only (its length
+    // on the device), with grids bounded by the longest list
+    const unsigned Gp = std::min(grid_of(a.pcap), 1024u);
+    const unsigned long long* np = &c->st->nprod;
+    hipLaunchKernelGGL(k_prod_counts, dim3(Gp), dim3(kBlock), 0, c->stream, a);
+    scan_u32(c, a.pci, a.ppi, a.pcap, np);
+    scan_u32(c, a.pce, a.ppe, a.pcap, np);
     hipLaunchKernelGGL(k_prod_commit, dim3(1), dim3(64), 0, c->stream, a);
-    hipLaunchKernelGGL(k_prod_place, dim3(grid_of(a.pcap)), dim3(kBlock), 0, c->stream, a);
+    hipLaunchKernelGGL(k_prod_place, dim3(Gp), dim3(kBlock), 0, c->stream, a);
 }
 
 // Fowler-Nordheim emission from the rings of the tip
