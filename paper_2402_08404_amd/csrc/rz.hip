@@ -27,7 +27,7 @@ using pic::kMe;
 using pic::kPi;
 using pic::kQe;
 
-constexpr int kCgBlocks = 256;  // blocks of the CG kernels (one partial each, summed in block order)
+constexpr int kCgBlocks = 1024;  // blocks of the CG kernels (one partial each, summed in a fixed order)
 constexpr uint8_t kFree = 0, kHeld0 = 1, kHeldV = 2;  // node types
 
 constexpr uint32_t kTagPairIon = 36, kTagIon = 37;  // the (e, Cu+) class: cell shift, pair draws
@@ -2042,7 +2042,7 @@ Lv level(const pic_rz_ctx* c, int l) {
 
 unsigned mg_grid(const Lv& L) {
     const int64_t nn = (int64_t)L.nr * L.nz;
-    return (unsigned)std::min<int64_t>(kCgBlocks * 4, std::max<int64_t>(1, (nn + kBlock - 1) / kBlock));
+    return (unsigned)std::min<int64_t>(1 << 14, std::max<int64_t>(1, (nn + kBlock - 1) / kBlock));  // a node a thread
 }
 
 // x_b = M b on level l (a V-cycle below it); x_a is work space
