@@ -675,19 +675,27 @@ __global__ __launch_bounds__(kMgLdsBlock) void k_mg_lds(MgLds m, const State* st
         L.type = sty + m.off[l];
         return L;
     };
-    for (int l = m.l0; l <= last; ++l) {
-        const int64_t nn = (int64_t)m.lv[l].nr * m.lv[l].nz;
-        for (int64_t n = t0; n < nn; n += T) sty[m.off[l] + n] = m.lv[l].type[n];
-    }
+    // the staging loops are unrolled so that several loads are in flight
+    // before the first LDS write (one loop over the types of all levels)
     {
-        const int64_t nn = (int64_t)m.lv[m.l0].nr * m.lv[m.l0].nz;
-        for (int64_t n = t0; n < nn; n += T) {
-            const double v = m.b[n];
-            sb[n] = m.lv[m.l0].type[n] == kFree ? v : 0.0;
+        const int ntot = m.off[last] + m.lv[last].nr * m.lv[last].nz;
+#pragma unroll 4
+        for (int q = (int)t0; q < ntot; q += (int)T) {
+            int l = m.l0;
+            while (l < last && q >= m.off[l + 1]) ++l;
+            sty[q] = m.lv[l].type[q - m.off[l]];
+        }
+        const int nb = m.lv[m.l0].nr * m.lv[m.l0].nz;
+#pragma unroll 4
+        for (int q = (int)t0; q < nb; q += (int)T) {
+            const double v = m.b[q];
+            const uint8_t t = m.lv[m.l0].type[q];
+            sb[q] = t == kFree ? v : 0.0;
         }
         if (m.inv) {
-            const int64_t nc = (int64_t)m.lv[last].nr * m.lv[last].nz;
-            for (int64_t q = t0; q < nc * nc; q += T) sinv[q] = m.inv[q];
+            const int nc = m.lv[last].nr * m.lv[last].nz;
+#pragma unroll 4
+            for (int q = (int)t0; q < nc * nc; q += (int)T) sinv[q] = m.inv[q];
         }
     }
     __syncthreads();
