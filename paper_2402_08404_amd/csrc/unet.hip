@@ -175,11 +175,19 @@ __host__ __device__ inline int conv3_tiles(const Geo& g) {
     return ((g.W + kTX - 1) / kTX) * ((g.H + kTY - 1) / kTY) * ((g.D + kTZ - 1) / kTZ) * g.B;
 }
 
-template <int NB>
-__global__ __launch_bounds__(256) void k_conv3_lds(ConvArgs p) {
-    __shared__ __align__(16) bf16_t tile[kHalo * kChunk];
+// The chunk width CH (8, 16 or 32) is fixed at compile time: a 32-wide
+// reduction step covers 32 / CH taps, so a lane's tap and channel follow
+// from shifts and the tap's halo offset from two multiply-shifts; the loads
+// of a chunk's halo tile are all issued before it is written to LDS, and the
+// B fragments of the next step are loaded while the current step's MFMAs
+// run. The LDS tile holds CH channels (13, 26 or 52 KB). On the small
+// levels the output channels are split over blockIdx.y (NB x 16 a block), so
+// that the grid fills the GPU.
+template <int NB, int CH>
+__global__ __launch_bounds__(256) void k_conv3_ch(ConvArgs p) {
+    static_assert(CH == 8 || CH == 16 || CH == 32, "chunk width");
+    __shared__ __align__(16) bf16_t tile[kHalo * CH];
     const int cin = p.ca + p.cb;
-    const int CH = cin < kChunk ? cin : kChunk;
     const Geo& g = p.g;
     const int ntx = (g.W + kTX - 1) / kTX, nty = (g.H + kTY - 1) / kTY, ntz = (g.D + kTZ - 1) / kTZ;
     int bid = blockIdx.x;
@@ -192,53 +200,96 @@ __global__ __launch_bounds__(256) void k_conv3_lds(ConvArgs p) {
     const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r16 = lane & 15, kg = 8 * (lane >> 4);
+    const int n0 = (int)blockIdx.y * NB * 16;  // the block's first output channel (channel groups along y)
+    constexpr int kSteps = (27 * CH + 31) / 32;  // reduction steps of one chunk
+    constexpr int kTapsPerStep = 32 / CH;
+    // the halo voxel of each of the wave's four M-tiles at tap offset zero
+    int base[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int m = wave + 4 * q;
+        const int lx = 16 * (m & 1) + r16, ly = (m >> 1) & 3, lz = m >> 3;
+        base[q] = ((lz + 1) * kHY + (ly + 1)) * kHX + (lx + 1);
+    }
+    // the lane's tap (valid or not), channel within the chunk and halo offset at step s
+    auto lane_tap = [&](int s, int& tap, int& cc, int& off) {
+        tap = s * kTapsPerStep + kg / CH;
+        cc = kg % CH;
+        const bool valid = tap < 27;  // past the last tap: a zero A fragment
+        if (!valid) tap = 0;
+        const int t = p.flip ? 26 - tap : tap;
+        const int dz = (t * 57) >> 9, r = t - 9 * dz;  // t / 9 and t % 9 for t < 27
+        const int dy = (r * 11) >> 5, dx = r - 3 * dy;  // r / 3 and r % 3 for r < 9
+        off = ((dz - 1) * kHY + (dy - 1)) * kHX + (dx - 1);
+        return valid;
+    };
     f32x4 acc[4][NB];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) acc[q][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
-    const int c8n = CH >> 3;
-    const int kspan = 27 * CH;  // reduction length of one chunk
+    constexpr int c8n = CH / 8;
+    constexpr int kLoads = (kHalo * c8n + 255) / 256;  // 16-byte loads a thread per chunk
     for (int c0 = 0; c0 < cin; c0 += CH) {
-        if (c0) __syncthreads();  // the previous chunk's reads are done
-        for (int e = threadIdx.x; e < kHalo * c8n; e += blockDim.x) {
+        // every load of the chunk's halo tile is issued before the first LDS
+        // write (the loop is unrolled into registers)
+        uint4 stage[kLoads];
+#pragma unroll
+        for (int it = 0; it < kLoads; ++it) {
+            const int e = (int)threadIdx.x + 256 * it;
             const int vox = e / c8n, c8 = (e - vox * c8n) * 8;
             const int hx = vox % kHX, hy = (vox / kHX) % kHY, hz = vox / (kHX * kHY);
             const int X = x0 + hx - 1, Y = y0 + hy - 1, Z = z0 + hz - 1;
-            uint4 raw = make_uint4(0, 0, 0, 0);
-            if (X >= 0 && X < g.W && Y >= 0 && Y < g.H && Z >= 0 && Z < g.D) {
+            stage[it] = make_uint4(0, 0, 0, 0);
+            if (e < kHalo * c8n && X >= 0 && X < g.W && Y >= 0 && Y < g.H && Z >= 0 && Z < g.D) {
                 const int64_t sv = (((int64_t)bsm * g.D + Z) * g.H + Y) * g.W + X;
                 const int ch = c0 + c8;
-                raw = ch < p.ca ? *(const uint4*)(p.a + sv * p.ca + ch) : *(const uint4*)(p.b + sv * p.cb + (ch - p.ca));
+                stage[it] = ch < p.ca ? *(const uint4*)(p.a + sv * p.ca + ch)
+                                      : *(const uint4*)(p.b + sv * p.cb + (ch - p.ca));
             }
-            *(uint4*)(tile + vox * CH + c8) = raw;
+        }
+        if (c0) __syncthreads();  // the previous chunk's reads are done
+#pragma unroll
+        for (int it = 0; it < kLoads; ++it) {
+            const int e = (int)threadIdx.x + 256 * it;
+            if (e < kHalo * c8n) *(uint4*)(tile + e * 8) = stage[it];  // (vox * CH + c8) = 8 e
         }
         __syncthreads();
-        for (int kc = 0; kc < kspan; kc += 32) {
-            const int kk = kc + kg;
-            const bool kv = kk < kspan;
-            const int tap = kv ? kk / CH : 0, cc = kv ? kk - tap * CH : 0;
-            const int t = p.flip ? 26 - tap : tap;
-            const int dx = t % 3 - 1, dy = (t / 3) % 3 - 1, dz = t / 9 - 1;
+        auto load_b = [&](int s, bf16x8* bv) {
+            int tap, cc, off;
+            lane_tap(s, tap, cc, off);
             const int64_t kw = (int64_t)tap * cin + c0 + cc;  // column of the packed weights
-            bf16x8 bv[NB];
 #pragma unroll
             for (int nb = 0; nb < NB; ++nb) {
-                uint4 wr = *(const uint4*)(p.w + (int64_t)(nb * 16 + r16) * p.Kpad + kw);
-                bv[nb] = *(bf16x8*)&wr;
+                const uint4 wr = *(const uint4*)(p.w + (int64_t)(n0 + nb * 16 + r16) * p.Kpad + kw);
+                bv[nb] = *(const bf16x8*)&wr;
             }
+        };
+        bf16x8 bcur[NB], bnext[NB];
+        load_b(0, bcur);
+        auto step = [&](int s) {
+            if (s + 1 < kSteps) load_b(s + 1, bnext);
+            int tap, cc, off;
+            const bool valid = lane_tap(s, tap, cc, off);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int m = wave + 4 * q;
-                const int lx = 16 * (m & 1) + r16, ly = (m >> 1) & 3, lz = m >> 3;
-                const int hv = ((lz + 1 + dz) * kHY + (ly + 1 + dy)) * kHX + (lx + 1 + dx);
                 uint4 raw = make_uint4(0, 0, 0, 0);
-                if (kv) raw = *(const uint4*)(tile + hv * CH + cc);
-                const bf16x8 av = *(bf16x8*)&raw;
+                if (valid) raw = *(const uint4*)(tile + (base[q] + off) * CH + cc);
+                const bf16x8 av = *(const bf16x8*)&raw;
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb)
-                    acc[q][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nb], acc[q][nb], 0, 0, 0);
+                    acc[q][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bcur[nb], acc[q][nb], 0, 0, 0);
             }
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) bcur[nb] = bnext[nb];
+        };
+        // (measured: the compiler's unrolling pays at 32 channels, a rolled
+        // loop with its higher occupancy at 8 and 16)
+        if constexpr (CH == 32) {
+            for (int s = 0; s < kSteps; ++s) step(s);
+        } else {
+#pragma unroll 1
+            for (int s = 0; s < kSteps; ++s) step(s);
         }
     }
 #pragma unroll
@@ -249,7 +300,7 @@ __global__ __launch_bounds__(256) void k_conv3_lds(ConvArgs p) {
         if (Y >= g.H || Z >= g.D) continue;
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            const int co = nb * 16 + r16;
+            const int co = n0 + nb * 16 + r16;
             const float bias = p.bias ? p.bias[co] : 0.f;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -869,15 +920,26 @@ static void launch_conv(unet* u, const UnetLayer& y, const bf16_t* a, const bf16
     int64_t M = (int64_t)g.B * g.D * g.H * g.W;
     const int cin = ca + cb;
     // every input-channel count here is 8 or a multiple of 32 (chunks of 32)
-    if (mode == kModeSame3 && (cin < kChunk ? cin % 8 == 0 : cin % kChunk == 0)) {
-        unsigned T = (unsigned)conv3_tiles(g);
-        switch (N / 16) {
-            case 1: hipLaunchKernelGGL(k_conv3_lds<1>, dim3(T), dim3(256), 0, u->stream, p); break;
-            case 2: hipLaunchKernelGGL(k_conv3_lds<2>, dim3(T), dim3(256), 0, u->stream, p); break;
-            case 4: hipLaunchKernelGGL(k_conv3_lds<4>, dim3(T), dim3(256), 0, u->stream, p); break;
-            case 8: hipLaunchKernelGGL(k_conv3_lds<8>, dim3(T), dim3(256), 0, u->stream, p); break;
-            default: u->err = "unsupported channel count"; break;
+    if (mode == kModeSame3 && (cin == 8 || cin == 16 || cin % kChunk == 0) &&
+        (N == 16 || N == 32 || N == 64 || N == 128)) {
+        const unsigned T = (unsigned)conv3_tiles(g);
+        const int ch = cin < kChunk ? cin : kChunk;
+        // output-channel groups: split while the grid has fewer than 512 blocks
+        int nb = N / 16, split = 1;
+        while (nb > 1 && T * split < 512u) {
+            nb /= 2;
+            split *= 2;
         }
+#define CONV3_CH(NB)                                                                                       \
+    (ch == 8 ? k_conv3_ch<NB, 8> : ch == 16 ? k_conv3_ch<NB, 16> : k_conv3_ch<NB, 32>)
+        const dim3 grid(T, (unsigned)split);
+        switch (nb) {
+            case 1: hipLaunchKernelGGL(CONV3_CH(1), grid, dim3(256), 0, u->stream, p); break;
+            case 2: hipLaunchKernelGGL(CONV3_CH(2), grid, dim3(256), 0, u->stream, p); break;
+            case 4: hipLaunchKernelGGL(CONV3_CH(4), grid, dim3(256), 0, u->stream, p); break;
+            default: hipLaunchKernelGGL(CONV3_CH(8), grid, dim3(256), 0, u->stream, p); break;
+        }
+#undef CONV3_CH
         return;
     }
     unsigned G = nblk(M, 64);
