@@ -156,6 +156,68 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs p) {
 }
 
 // ---------------------------------------------------------------------------
+// Up convolution (forward), all eight parities in one launch: each wave's 16
+// coarse voxels are read once (their KS x 32 input channels kept in
+// registers) and multiplied by the eight parities' weight slices in turn
+// (slice par at w + par N Kpad), each writing its fine voxels 2 v + par.
+template <int NB, int KS>
+__global__ __launch_bounds__(256) void k_up2_all(ConvArgs p) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const Geo& g = p.g;
+    const int64_t M = (int64_t)g.B * g.D * g.H * g.W;
+    const int64_t row0 = (int64_t)blockIdx.x * 64 + wave * 16;
+    const int64_t v = row0 + (lane & 15);
+    const int kg = 8 * (lane >> 4);
+    bf16x8 av[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int ci = 32 * ks + kg;
+        uint4 raw = make_uint4(0, 0, 0, 0);
+        if (v < M) raw = ci < p.ca ? *(const uint4*)(p.a + v * p.ca + ci) : *(const uint4*)(p.b + v * p.cb + (ci - p.ca));
+        av[ks] = *(const bf16x8*)&raw;
+    }
+    // the coarse coordinates of the lane's four output rows
+    int cx[4], cy[4], cz[4], cb[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        int64_t r = row0 + 4 * (lane >> 4) + j;
+        cx[j] = (int)(r % g.W);
+        r /= g.W;
+        cy[j] = (int)(r % g.H);
+        r /= g.H;
+        cz[j] = (int)(r % g.D);
+        cb[j] = (int)(r / g.D);
+    }
+    for (int par = 0; par < 8; ++par) {
+        const bf16_t* w = p.w + (int64_t)par * p.N * p.Kpad;
+        f32x4 acc[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) acc[nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const uint4 wr = *(const uint4*)(w + (int64_t)(nb * 16 + (lane & 15)) * p.Kpad + 32 * ks + kg);
+                acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[ks], *(const bf16x8*)&wr, acc[nb], 0, 0, 0);
+            }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+            const int co = nb * 16 + (lane & 15);
+            const float bias = p.bias ? p.bias[co] : 0.f;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (row0 + 4 * (lane >> 4) + j >= M) continue;
+                float val = acc[nb][j] + bias;
+                if (p.relu) val = val > 0.f ? val : 0.f;
+                const int X = 2 * cx[j] + (par & 1), Y = 2 * cy[j] + ((par >> 1) & 1), Z = 2 * cz[j] + (par >> 2);
+                const int64_t o = (((int64_t)cb[j] * (2 * g.D) + Z) * (2 * g.H) + Y) * (2 * g.W) + X;
+                p.out[o * p.N + co] = f2bf(val);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // 3x3x3 convolution (forward, or input gradient with flip) with the input
 // tile in LDS. A block owns an output tile of 32 x 4 x 2 voxels (x, y, z):
 // 256 GEMM rows = 16 M-tiles of 16 consecutive x voxels, wave w taking
@@ -1062,7 +1124,29 @@ pic_status unet_forward(unet* u, const float* x, float* y) {
         const bf16_t* b = l.in_b >= 0 ? u->act[l.in_b] : nullptr;
         int cin = l.ca + l.cb;
         const float* bias = u->params + l.b_off;
-        if (l.mode == kModeUp2) {
+        if (l.mode == kModeUp2 && l.Kf == cin && ((l.cout == 16 && cin == 32) || (l.cout == 32 && cin == 64) ||
+                                                  (l.cout == 64 && cin == 128))) {
+            // the eight parities in one launch (the argument set of launch_conv)
+            ConvArgs p{};
+            p.a = a;
+            p.b = b;
+            p.w = l.wf;
+            p.bias = bias;
+            p.out = u->act[l.out];
+            p.ca = l.ca;
+            p.cb = l.cb;
+            p.N = l.cout;
+            p.K = cin;
+            p.Kpad = l.Kf;
+            p.mode = kModeUp2;
+            p.relu = l.relu;
+            p.g = l.g;
+            const int64_t M = (int64_t)l.g.B * l.g.D * l.g.H * l.g.W;
+            const unsigned G = nblk(M, 64);
+            if (l.cout == 16) hipLaunchKernelGGL((k_up2_all<1, 1>), dim3(G), dim3(256), 0, u->stream, p);
+            else if (l.cout == 32) hipLaunchKernelGGL((k_up2_all<2, 2>), dim3(G), dim3(256), 0, u->stream, p);
+            else hipLaunchKernelGGL((k_up2_all<4, 4>), dim3(G), dim3(256), 0, u->stream, p);
+        } else if (l.mode == kModeUp2) {
             for (int par = 0; par < 8; ++par)
                 launch_conv(u, l, a, b, l.wf + (int64_t)par * l.cout * l.Kf, l.ca, l.cb, l.cout, cin, l.Kf, kModeUp2,
                             l.relu, 0, par, l.g, bias, u->act[l.out], nullptr, 0);
