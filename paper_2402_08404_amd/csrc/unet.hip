@@ -113,16 +113,38 @@ __global__ __launch_bounds__(256) void k_conv(ConvArgs p) {
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
     const int kg = 8 * (lane >> 4);
+    // the row's voxel coordinates, once (not per reduction step)
+    const Geo& g = p.g;
+    int x = 0, y = 0, z = 0, bsm = 0;
+    {
+        int64_t r = vrow ? v : 0;
+        x = (int)(r % g.W);
+        r /= g.W;
+        y = (int)(r % g.H);
+        r /= g.H;
+        z = (int)(r % g.D);
+        bsm = (int)(r / g.D);
+    }
     for (int kc = 0; kc < p.Kpad; kc += 32) {
         int k0 = kc + kg;
         bf16x8 av;
         uint4 raw = make_uint4(0, 0, 0, 0);
         if (vrow && k0 < p.K) {
-            int tap = k0 / cin, ci = k0 - tap * cin;
-            bool ok;
-            int s = src_voxel(p, v, tap, ok);
-            if (ok) {
-                const bf16_t* src = ci < p.ca ? p.a + (int64_t)s * p.ca + ci : p.b + (int64_t)s * p.cb + (ci - p.ca);
+            const int tap = k0 / cin, ci = k0 - tap * cin;
+            int sx = x, sy = y, sz = z;  // kModeUp2: the row's own voxel
+            if (p.mode == kModeSame3) {
+                const int t = p.flip ? 26 - tap : tap;
+                sx += t % 3 - 1;
+                sy += (t / 3) % 3 - 1;
+                sz += t / 9 - 1;
+            } else if (p.mode == kModeDown2) {
+                sx = 2 * x + (tap & 1);
+                sy = 2 * y + ((tap >> 1) & 1);
+                sz = 2 * z + ((tap >> 2) & 1);
+            }
+            if (sx >= 0 && sx < g.iW && sy >= 0 && sy < g.iH && sz >= 0 && sz < g.iD) {
+                const int64_t sv = (((int64_t)bsm * g.iD + sz) * g.iH + sy) * g.iW + sx;
+                const bf16_t* src = ci < p.ca ? p.a + sv * p.ca + ci : p.b + sv * p.cb + (ci - p.ca);
                 raw = *(const uint4*)src;
             }
         }
