@@ -227,6 +227,42 @@ def test_rz_field_ionization_parity():
     assert o.events[4] > 40, o.events
 
 
+def test_rz_many_products_parity():
+    """About 11 000 impact ionizations in one stage (ionization cross
+    section scaled up 10^6, electrons and neutrals in the same 200 cells):
+    a product list longer than the in-LDS sort (4096 entries) and prefix sums
+    over several chunks of the product list; states, events and products by
+    id as the oracle's, twice."""
+    print("case: rz many products", flush=True)
+    el, iz, cx = W.synthetic_tables()
+    tabs = (1e-2, 1e4, el, iz * 1e6, cx)
+    geom = dict(GEOM)
+    o = RZ(geom["nr"], geom["nz"], geom["h"], geom["tip_r"], geom["tip_h"], geom["apex_field"], geom["dt"],
+           geom["m_ion"], seed=3, xs=tabs, fn_rings=16)
+    rng = np.random.default_rng(3)
+    n = 12000
+    v = 0.1  # grid units a step: about 45 eV electrons
+    load = {0: {"r": rng.uniform(10, 20, n), "z": rng.uniform(50, 70, n), "vr": rng.normal(0, v, n),
+                "vt": rng.normal(0, v, n), "vz": rng.normal(0, v, n)},
+            1: {k: np.zeros(0) for k in ("r", "z", "vr", "vt", "vz")},
+            2: {"r": rng.uniform(10, 20, n), "z": rng.uniform(50, 70, n), "vr": np.zeros(n), "vt": np.zeros(n),
+                "vz": np.zeros(n)}}
+    o.load(0, load[0], np.arange(n))
+    o.load(2, load[2], np.arange(n, 2 * n))
+    g = rz.RZSimulation(**geom, load=load, laplace_rtol=1e-13, step_rtol=1e-14, seed=3, xs=tabs, fn_rings=0,
+                        caps=[40000, 16000, n + 1])
+    g.set_phi(o.phi)
+    for step in range(2):
+        g.step(1, rz.PIC_RZ_COLLIDE | rz.PIC_RZ_ADVANCE)
+        o.collide()
+        o.step_no += 1
+        _compare_all(g, o, 1e-12)
+        m = g.moments()
+        assert np.array_equal(m["events"], o.events), (m["events"], o.events)
+        assert m["next_id"] == o.next_id
+    assert o.events[2] > 8000, o.events
+
+
 def test_rz_emission_parity():
     print("case: rz emission", flush=True)
     load = {s: {k: np.zeros(0) for k in ("r", "z", "vr", "vt", "vz")} for s in range(3)}
