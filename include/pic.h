@@ -390,7 +390,9 @@ typedef struct unet unet;
 
 /* Number of fp32 parameters. */
 pic_status unet_param_count(const pic_unet_config* cfg, int64_t* n);
-/* Bytes of device work memory for a network over batch x d x h x w inputs. */
+/* Bytes of device work memory for a network over batch x d x h x w inputs
+ * (d, h, w multiples of 8, at least 8; batch d h w below 2^31).
+ * INVALID_ARG otherwise. */
 pic_status unet_workspace_size(const pic_unet_config* cfg, int32_t batch, int32_t d, int32_t h, int32_t w,
                                size_t* bytes);
 /* Create a network over caller-owned device memory: params and grads hold

@@ -61,14 +61,21 @@ struct ConvArgs {
     Geo g;
 };
 
+// (x, y, z, sample) of row v, in 32-bit arithmetic (every tensor of the
+// network holds fewer than 2^31 voxels)
+__device__ inline void row_coords(const Geo& g, int64_t v, int& x, int& y, int& z, int& bsm) {
+    const uint32_t u = (uint32_t)v, W = (uint32_t)g.W, H = (uint32_t)g.H, D = (uint32_t)g.D;
+    const uint32_t q = u / W, q2 = q / H, q3 = q2 / D;
+    x = (int)(u - q * W);
+    y = (int)(q - q2 * H);
+    z = (int)(q2 - q3 * D);
+    bsm = (int)q3;
+}
+
 __device__ inline int src_voxel(const ConvArgs& p, int64_t v, int tap, bool& ok) {
     const Geo& g = p.g;
-    int x = (int)(v % g.W);
-    int64_t r = v / g.W;
-    int y = (int)(r % g.H);
-    r /= g.H;
-    int z = (int)(r % g.D);
-    int bsm = (int)(r / g.D);
+    int x, y, z, bsm;
+    row_coords(g, v, x, y, z, bsm);
     int sx, sy, sz;
     if (p.mode == kModeSame3) {
         int t = p.flip ? 26 - tap : tap;
@@ -91,12 +98,8 @@ __device__ inline int src_voxel(const ConvArgs& p, int64_t v, int tap, bool& ok)
 __device__ inline int64_t out_voxel(const ConvArgs& p, int64_t v) {
     if (p.mode != kModeUp2) return v;
     const Geo& g = p.g;
-    int x = (int)(v % g.W);
-    int64_t r = v / g.W;
-    int y = (int)(r % g.H);
-    r /= g.H;
-    int z = (int)(r % g.D);
-    int bsm = (int)(r / g.D);
+    int x, y, z, bsm;
+    row_coords(g, v, x, y, z, bsm);
     int X = 2 * x + (p.par & 1), Y = 2 * y + ((p.par >> 1) & 1), Z = 2 * z + ((p.par >> 2) & 1);
     return (((int64_t)bsm * (2 * g.D) + Z) * (2 * g.H) + Y) * (2 * g.W) + X;
 }
@@ -637,6 +640,134 @@ __global__ __launch_bounds__(256) void k_wgrad2(WgradArgs p) {
     }
 }
 
+// Weight gradient of a 3x3x3 convolution in one pass over the voxels for
+// all 27 taps: a block takes output tiles of 32 x 4 x 2 voxels in turn
+// (tile = blockIdx.x, blockIdx.x + gridDim.x, ...), stages the tile's input
+// with its one-voxel halo (CH channels) and its output gradient (NT x 16
+// channels) in LDS, and adds A(v + offset(tap))[ci] G(v)[co] over the tile's
+// 256 voxels for every tap (wave w taking taps w, w + 4, ...), eight voxels
+// of one x row per lane and reduction step. The block's sums go to
+// part[block][tap][ci][co], summed over the blocks in a fixed order after.
+template <int CH, int NT>
+__global__ __launch_bounds__(256) void k_wgrad3(WgradArgs p) {
+    static_assert(CH == 16 || CH == 32, "input channels");
+    constexpr int NC = NT * 16;
+    constexpr int CT = CH / 16;                 // ci tiles
+    constexpr int kTapsW = 7;                   // taps of a wave (at most)
+    __shared__ __align__(16) bf16_t As[kHalo * CH];
+    __shared__ __align__(16) bf16_t Gs[kTX * kTY * kTZ * NC];
+    const Geo& g = p.g;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r16 = lane & 15, kg = 8 * (lane >> 4);
+    const int ntx = (g.W + kTX - 1) / kTX, nty = (g.H + kTY - 1) / kTY, ntz = (g.D + kTZ - 1) / kTZ;
+    const int ntiles = ntx * nty * ntz * g.B;
+    f32x4 acc[kTapsW][CT][NT];
+#pragma unroll
+    for (int i = 0; i < kTapsW; ++i)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int n = 0; n < NT; ++n) acc[i][c][n] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    constexpr int c8a = CH / 8, c8g = NC / 8;
+    constexpr int kLoadA = (kHalo * c8a + 255) / 256, kLoadG = (kTX * kTY * kTZ * c8g + 255) / 256;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        int bid = tile;
+        const int tx = bid % ntx;
+        bid /= ntx;
+        const int ty = bid % nty;
+        bid /= nty;
+        const int tz = bid % ntz;
+        const int bsm = bid / ntz;
+        const int x0 = tx * kTX, y0 = ty * kTY, z0 = tz * kTZ;
+        // every load of the tile issued before the first LDS write
+        uint4 sa[kLoadA], sg[kLoadG];
+#pragma unroll
+        for (int it = 0; it < kLoadA; ++it) {
+            const int e = (int)threadIdx.x + 256 * it;
+            const int vox = e / c8a, c8 = (e - vox * c8a) * 8;
+            const int hx = vox % kHX, hy = (vox / kHX) % kHY, hz = vox / (kHX * kHY);
+            const int X = x0 + hx - 1, Y = y0 + hy - 1, Z = z0 + hz - 1;
+            sa[it] = make_uint4(0, 0, 0, 0);
+            if (e < kHalo * c8a && X >= 0 && X < g.W && Y >= 0 && Y < g.H && Z >= 0 && Z < g.D) {
+                const int64_t sv = (((int64_t)bsm * g.D + Z) * g.H + Y) * g.W + X;
+                sa[it] = c8 < p.ca ? *(const uint4*)(p.a + sv * p.ca + c8)
+                                   : *(const uint4*)(p.b + sv * p.cb + (c8 - p.ca));
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < kLoadG; ++it) {
+            const int e = (int)threadIdx.x + 256 * it;
+            const int vox = e / c8g, c8 = (e - vox * c8g) * 8;
+            const int lx = vox % kTX, ly = (vox / kTX) % kTY, lz = vox / (kTX * kTY);
+            const int X = x0 + lx, Y = y0 + ly, Z = z0 + lz;
+            sg[it] = make_uint4(0, 0, 0, 0);
+            if (e < kTX * kTY * kTZ * c8g && X < g.W && Y < g.H && Z < g.D) {
+                const int64_t v = (((int64_t)bsm * g.D + Z) * g.H + Y) * g.W + X;
+                sg[it] = *(const uint4*)(p.gr + v * NC + c8);
+            }
+        }
+        __syncthreads();  // the previous tile's LDS reads are done
+#pragma unroll
+        for (int it = 0; it < kLoadA; ++it) {
+            const int e = (int)threadIdx.x + 256 * it;
+            if (e < kHalo * c8a) *(uint4*)(As + 8 * e) = sa[it];
+        }
+#pragma unroll
+        for (int it = 0; it < kLoadG; ++it) {
+            const int e = (int)threadIdx.x + 256 * it;
+            if (e < kTX * kTY * kTZ * c8g) *(uint4*)(Gs + 8 * e) = sg[it];
+        }
+        __syncthreads();
+        // reduction steps: the 8 x rows of the tile, 32 voxels each
+        for (int row = 0; row < kTY * kTZ; ++row) {
+            const int ly = row % kTY, lz = row / kTY;
+            bf16x8 bv[NT];
+#pragma unroll
+            for (int n = 0; n < NT; ++n)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const bf16_t y = Gs[(row * kTX + kg + j) * NC + n * 16 + r16];
+                    bv[n][j] = *(const __bf16*)&y;
+                }
+            const int hrow = ((lz + 1) * kHY + (ly + 1)) * kHX + 1 + kg;  // halo voxel of x = kg, offset zero
+#pragma unroll
+            for (int i = 0; i < kTapsW; ++i) {
+                const int t = wave + 4 * i;
+                if (t >= 27) break;
+                const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+                const int h0 = hrow + (dz * kHY + dy) * kHX + dx;
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    bf16x8 av;
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const bf16_t x = As[(h0 + j) * CH + c * 16 + r16];
+                        av[j] = *(const __bf16*)&x;
+                    }
+#pragma unroll
+                    for (int n = 0; n < NT; ++n)
+                        acc[i][c][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[n], acc[i][c][n], 0, 0, 0);
+                }
+            }
+        }
+    }
+    float* base = p.part + (int64_t)blockIdx.x * 27 * CH * NC;
+#pragma unroll
+    for (int i = 0; i < kTapsW; ++i) {
+        const int t = wave + 4 * i;
+        if (t >= 27) break;
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int n = 0; n < NT; ++n)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int ci = c * 16 + 4 * (lane >> 4) + j, co = n * 16 + r16;
+                    base[((int64_t)t * CH + ci) * NC + co] = acc[i][c][n][j];
+                }
+    }
+}
+
 // gW[i] = sum over splits of part[s][i] (fixed order)
 __global__ void k_sum_splits(const float* part, int nsplit, int64_t n, float* gw) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -951,6 +1082,13 @@ static Plan make_plan(const pic_unet_config* c, int B, int D, int H, int W) {
     return p;
 }
 
+// Layers whose weight gradient takes the one-pass kernel k_wgrad3, and its
+// block count (one partial sum set each)
+static bool wgrad3_ok(int mode, int taps, int cin, int N) {
+    return mode == kModeSame3 && taps == 27 && (cin == 16 || cin == 32) && (N == 16 || N == 32);
+}
+static int64_t wgrad3_blocks(const Geo& g) { return std::min<int64_t>(1024, conv3_tiles(g)); }
+
 static int64_t wgrad_splits(int64_t M) {
     int64_t s = (M + 4095) / 4096;
     return s < 1 ? 1 : (s > 256 ? 256 : s);
@@ -971,6 +1109,8 @@ static size_t plan_bytes(const Plan& p, int64_t vox0) {
         maxe = std::max<int64_t>(maxe, (y.mode == kModeUp2 ? 8 * rows : rows) * std::max(y.cout, y.ca + y.cb));
         int64_t taps = y.mode == kModeUp2 ? 8 : y.taps;
         maxpart = std::max<int64_t>(maxpart, wgrad_splits(rows) * taps * (y.ca + y.cb) * y.cout);
+        if (wgrad3_ok(y.mode, (int)taps, y.ca + y.cb, y.cout))
+            maxpart = std::max<int64_t>(maxpart, wgrad3_blocks(y.g) * 27 * (y.ca + y.cb) * y.cout);
     }
     maxpart = std::max<int64_t>(maxpart, std::max<int64_t>(((vox0 + 255) / 256) * 64, 1024 * 128));
     b += al(maxe * 2) + 2 * al(maxe * 4) + al(maxpart * 4) + 2 * al(p.nparams * 4) + 2 * al(vox0 * 4) +
@@ -1058,6 +1198,7 @@ pic_status unet_param_count(const pic_unet_config* c, int64_t* n) {
 
 pic_status unet_workspace_size(const pic_unet_config* c, int batch, int d, int h, int w, size_t* bytes) {
     if (!c || !bytes || batch < 1 || d < 8 || h < 8 || w < 8 || d % 8 || h % 8 || w % 8) return PIC_E_INVALID_ARG;
+    if ((int64_t)batch * d * h * w >= ((int64_t)1 << 31)) return PIC_E_INVALID_ARG;  // 32-bit voxel indices
     if (c->base_channels != 16) return PIC_E_INVALID_ARG;
     Plan p = make_plan(c, batch, d, h, w);
     *bytes = plan_bytes(p, (int64_t)batch * d * h * w);
@@ -1105,6 +1246,8 @@ pic_status unet_create(const pic_unet_config* c, float* params, float* grads, vo
         maxe = std::max<int64_t>(maxe, (y.mode == kModeUp2 ? 8 * rows : rows) * std::max(y.cout, y.ca + y.cb));
         int64_t taps = y.mode == kModeUp2 ? 8 : y.taps;
         maxpart = std::max<int64_t>(maxpart, wgrad_splits(rows) * taps * (y.ca + y.cb) * y.cout);
+        if (wgrad3_ok(y.mode, (int)taps, y.ca + y.cb, y.cout))
+            maxpart = std::max<int64_t>(maxpart, wgrad3_blocks(y.g) * 27 * (y.ca + y.cb) * y.cout);
     }
     int64_t vox0 = (int64_t)batch * d * h * w;
     maxpart = std::max<int64_t>(maxpart, std::max<int64_t>(((vox0 + 255) / 256) * 64, 1024 * 128));
@@ -1200,6 +1343,19 @@ static void launch_wgrad(unet* u, const UnetLayer& l, const bf16_t* a, const bf1
     w.par = par;
     w.g = g;
     int64_t rows = (int64_t)g.B * g.D * g.H * g.W;
+    const int cin = l.ca + l.cb;
+    if (wgrad3_ok(l.mode, taps, cin, l.cout)) {
+        const int64_t nb = wgrad3_blocks(g);
+        const dim3 G((unsigned)nb);
+        if (cin == 16 && l.cout == 16) hipLaunchKernelGGL((k_wgrad3<16, 1>), G, dim3(256), 0, u->stream, w);
+        else if (cin == 16) hipLaunchKernelGGL((k_wgrad3<16, 2>), G, dim3(256), 0, u->stream, w);
+        else if (l.cout == 16) hipLaunchKernelGGL((k_wgrad3<32, 1>), G, dim3(256), 0, u->stream, w);
+        else hipLaunchKernelGGL((k_wgrad3<32, 2>), G, dim3(256), 0, u->stream, w);
+        const int64_t n = (int64_t)27 * cin * l.cout;
+        hipLaunchKernelGGL(k_sum_splits, dim3(nblk(n)), dim3(256), 0, u->stream, (const float*)u->part, (int)nb, n,
+                           dst);
+        return;
+    }
     int64_t ns = wgrad_splits(rows);
     w.rows_per_split = (rows + ns - 1) / ns;
     const int cin16 = (l.ca + l.cb + 15) / 16 * 16;
