@@ -650,9 +650,9 @@ __global__ __launch_bounds__(256) void k_wgrad2(WgradArgs p) {
 // part[block][tap][ci][co], summed over the blocks in a fixed order after.
 template <int CH, int NT>
 __global__ __launch_bounds__(256) void k_wgrad3(WgradArgs p) {
-    static_assert(CH == 16 || CH == 32, "input channels");
+    static_assert(CH == 8 || CH == 16 || CH == 32, "input channels");
     constexpr int NC = NT * 16;
-    constexpr int CT = CH / 16;                 // ci tiles
+    constexpr int CT = (CH + 15) / 16;          // ci tiles (rows past CH are zero)
     constexpr int kTapsW = 7;                   // taps of a wave (at most)
     __shared__ __align__(16) bf16_t As[kHalo * CH];
     __shared__ __align__(16) bf16_t Gs[kTX * kTY * kTZ * NC];
@@ -739,9 +739,10 @@ __global__ __launch_bounds__(256) void k_wgrad3(WgradArgs p) {
 #pragma unroll
                 for (int c = 0; c < CT; ++c) {
                     bf16x8 av;
+                    const int ci = c * 16 + r16;
 #pragma unroll
                     for (int j = 0; j < 8; ++j) {
-                        const bf16_t x = As[(h0 + j) * CH + c * 16 + r16];
+                        const bf16_t x = ci < CH ? As[(h0 + j) * CH + ci] : (bf16_t)0;
                         av[j] = *(const __bf16*)&x;
                     }
 #pragma unroll
@@ -763,7 +764,7 @@ __global__ __launch_bounds__(256) void k_wgrad3(WgradArgs p) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int ci = c * 16 + 4 * (lane >> 4) + j, co = n * 16 + r16;
-                    base[((int64_t)t * CH + ci) * NC + co] = acc[i][c][n][j];
+                    if (ci < CH) base[((int64_t)t * CH + ci) * NC + co] = acc[i][c][n][j];
                 }
     }
 }
@@ -861,6 +862,46 @@ __global__ void k_head_back(const bf16_t* y, int C, const float* w, const float*
     }
     float t = pic::block_sum(d, sh);
     if (threadIdx.x == 0) part[(int64_t)blockIdx.x * (C + 1) + C] = t;
+}
+
+// The same for C = 16 channels: each thread reads its voxel's 16 channels in
+// two 16-byte loads and writes dy in four, and the 17 sums of the block are
+// formed together (wavefront butterflies, then the four wavefronts' values
+// added in wave order by 17 threads), one barrier instead of seventeen pairs.
+__global__ __launch_bounds__(256) void k_head_back16(const bf16_t* y, const float* w, const float* dout, int64_t n,
+                                                     float* dy, float* part) {
+    __shared__ float sh[4][17];
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool in = v < n;
+    const float d = in ? dout[v] : 0.f;
+    float yc[16];
+    if (in) {
+        const uint4 r0 = *(const uint4*)(y + v * 16), r1 = *(const uint4*)(y + v * 16 + 8);
+        const uint32_t u[8] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w};
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            yc[2 * k] = __uint_as_float(u[k] << 16);
+            yc[2 * k + 1] = __uint_as_float(u[k] & 0xFFFF0000u);
+        }
+        float4* o = (float4*)(dy + v * 16);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o[q] = make_float4(d * w[4 * q], d * w[4 * q + 1], d * w[4 * q + 2], d * w[4 * q + 3]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 16; ++c) yc[c] = 0.f;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < 17; ++c) {
+        const float t = pic::wave_sum(c < 16 ? d * yc[c] : d);
+        if (lane == 0) sh[wv][c] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < 17) {
+        float t = 0.f;
+        for (int q = 0; q < 4; ++q) t += sh[q][threadIdx.x];
+        part[(int64_t)blockIdx.x * 17 + threadIdx.x] = t;
+    }
 }
 
 // out[c] = sum over rows of part[r][c]: one block per column, each thread
@@ -1085,7 +1126,7 @@ static Plan make_plan(const pic_unet_config* c, int B, int D, int H, int W) {
 // Layers whose weight gradient takes the one-pass kernel k_wgrad3, and its
 // block count (one partial sum set each)
 static bool wgrad3_ok(int mode, int taps, int cin, int N) {
-    return mode == kModeSame3 && taps == 27 && (cin == 16 || cin == 32) && (N == 16 || N == 32);
+    return mode == kModeSame3 && taps == 27 && (cin == 8 || cin == 16 || cin == 32) && (N == 16 || N == 32);
 }
 static int64_t wgrad3_blocks(const Geo& g) { return std::min<int64_t>(1024, conv3_tiles(g)); }
 
@@ -1347,7 +1388,9 @@ static void launch_wgrad(unet* u, const UnetLayer& l, const bf16_t* a, const bf1
     if (wgrad3_ok(l.mode, taps, cin, l.cout)) {
         const int64_t nb = wgrad3_blocks(g);
         const dim3 G((unsigned)nb);
-        if (cin == 16 && l.cout == 16) hipLaunchKernelGGL((k_wgrad3<16, 1>), G, dim3(256), 0, u->stream, w);
+        if (cin == 8 && l.cout == 16) hipLaunchKernelGGL((k_wgrad3<8, 1>), G, dim3(256), 0, u->stream, w);
+        else if (cin == 8) hipLaunchKernelGGL((k_wgrad3<8, 2>), G, dim3(256), 0, u->stream, w);
+        else if (cin == 16 && l.cout == 16) hipLaunchKernelGGL((k_wgrad3<16, 1>), G, dim3(256), 0, u->stream, w);
         else if (cin == 16) hipLaunchKernelGGL((k_wgrad3<16, 2>), G, dim3(256), 0, u->stream, w);
         else if (l.cout == 16) hipLaunchKernelGGL((k_wgrad3<32, 1>), G, dim3(256), 0, u->stream, w);
         else hipLaunchKernelGGL((k_wgrad3<32, 2>), G, dim3(256), 0, u->stream, w);
@@ -1381,7 +1424,11 @@ pic_status unet_backward(unet* u, const float* target, double* loss) {
     for (size_t i = 0; i < u->act.size(); ++i)
         (void)pic::launch_zero(u->gact[i], (size_t)u->act_n[i] * u->act_c[i] * 4, u->stream);
     int Ch = u->act_c[u->head_in];
-    hipLaunchKernelGGL(k_head_back, dim3(nb0), dim3(256), 0, u->stream, (const bf16_t*)u->act[u->head_in], Ch,
+    if (Ch == 16)
+        hipLaunchKernelGGL(k_head_back16, dim3(nb0), dim3(256), 0, u->stream, (const bf16_t*)u->act[u->head_in],
+                           u->params + u->head_w, (const float*)u->dout, n0, u->gact[u->head_in], u->part);
+    else
+        hipLaunchKernelGGL(k_head_back, dim3(nb0), dim3(256), 0, u->stream, (const bf16_t*)u->act[u->head_in], Ch,
                        (const float*)(u->params + u->head_w), (const float*)u->dout, n0, u->gact[u->head_in], u->part);
     hipLaunchKernelGGL(k_sum_cols, dim3(Ch + 1), dim3(256), 0, u->stream, (const float*)u->part, (int)nb0, Ch + 1,
                        u->grads + u->head_w);  // head_b follows head_w
