@@ -770,11 +770,20 @@ __global__ __launch_bounds__(256) void k_wgrad3(WgradArgs p) {
 }
 
 // gW[i] = sum over splits of part[s][i] (fixed order)
+// (eight loads in flight, added in split order)
 __global__ void k_sum_splits(const float* part, int nsplit, int64_t n, float* gw) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     float s = 0.f;
-    for (int k = 0; k < nsplit; ++k) s += part[(int64_t)k * n + i];
+    int k = 0;
+    for (; k + 8 <= nsplit; k += 8) {
+        float t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = part[(int64_t)(k + u) * n + i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += t[u];
+    }
+    for (; k < nsplit; ++k) s += part[(int64_t)k * n + i];
     gw[i] = s;
 }
 
@@ -1131,7 +1140,7 @@ static bool wgrad3_ok(int mode, int taps, int cin, int N) {
 static int64_t wgrad3_blocks(const Geo& g) { return std::min<int64_t>(1024, conv3_tiles(g)); }
 
 static int64_t wgrad_splits(int64_t M) {
-    int64_t s = (M + 4095) / 4096;
+    int64_t s = (M + 511) / 512;  // (small levels: enough blocks to fill the GPU)
     return s < 1 ? 1 : (s > 256 ? 256 : s);
 }
 
