@@ -646,7 +646,8 @@ __global__ __launch_bounds__(256) void k_wgrad2(WgradArgs p) {
 // with its one-voxel halo (CH channels) and its output gradient (NT x 16
 // channels) in LDS, and adds A(v + offset(tap))[ci] G(v)[co] over the tile's
 // 256 voxels for every tap (wave w taking taps w, w + 4, ...), eight voxels
-// of one x row per lane and reduction step. The block's sums go to
+// of one x row per lane and reduction step. The input channels are taken CH
+// at a time, chunk blockIdx.y. The block's sums go to
 // part[block][tap][ci][co], summed over the blocks in a fixed order after.
 template <int CH, int NT>
 __global__ __launch_bounds__(256) void k_wgrad3(WgradArgs p) {
@@ -661,6 +662,7 @@ __global__ __launch_bounds__(256) void k_wgrad3(WgradArgs p) {
     const int r16 = lane & 15, kg = 8 * (lane >> 4);
     const int ntx = (g.W + kTX - 1) / kTX, nty = (g.H + kTY - 1) / kTY, ntz = (g.D + kTZ - 1) / kTZ;
     const int ntiles = ntx * nty * ntz * g.B;
+    const int cin = p.ca + p.cb, c0 = (int)blockIdx.y * CH;  // all input channels; the block's first
     f32x4 acc[kTapsW][CT][NT];
 #pragma unroll
     for (int i = 0; i < kTapsW; ++i)
@@ -690,8 +692,9 @@ __global__ __launch_bounds__(256) void k_wgrad3(WgradArgs p) {
             sa[it] = make_uint4(0, 0, 0, 0);
             if (e < kHalo * c8a && X >= 0 && X < g.W && Y >= 0 && Y < g.H && Z >= 0 && Z < g.D) {
                 const int64_t sv = (((int64_t)bsm * g.D + Z) * g.H + Y) * g.W + X;
-                sa[it] = c8 < p.ca ? *(const uint4*)(p.a + sv * p.ca + c8)
-                                   : *(const uint4*)(p.b + sv * p.cb + (c8 - p.ca));
+                const int ch = c0 + c8;
+                sa[it] = ch < p.ca ? *(const uint4*)(p.a + sv * p.ca + ch)
+                                   : *(const uint4*)(p.b + sv * p.cb + (ch - p.ca));
             }
         }
 #pragma unroll
@@ -752,7 +755,7 @@ __global__ __launch_bounds__(256) void k_wgrad3(WgradArgs p) {
             }
         }
     }
-    float* base = p.part + (int64_t)blockIdx.x * 27 * CH * NC;
+    float* base = p.part + (int64_t)blockIdx.x * 27 * cin * NC;
 #pragma unroll
     for (int i = 0; i < kTapsW; ++i) {
         const int t = wave + 4 * i;
@@ -764,7 +767,7 @@ __global__ __launch_bounds__(256) void k_wgrad3(WgradArgs p) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int ci = c * 16 + 4 * (lane >> 4) + j, co = n * 16 + r16;
-                    if (ci < CH) base[((int64_t)t * CH + ci) * NC + co] = acc[i][c][n][j];
+                    if (ci < CH) base[((int64_t)t * cin + c0 + ci) * NC + co] = acc[i][c][n][j];
                 }
     }
 }
@@ -1132,10 +1135,20 @@ static Plan make_plan(const pic_unet_config* c, int B, int D, int H, int W) {
     return p;
 }
 
-// Layers whose weight gradient takes the one-pass kernel k_wgrad3, and its
-// block count (one partial sum set each)
+// Layers whose weight gradient takes the one-pass kernel k_wgrad3 (staged
+// channels ch a block, chunks of them along y), and its block count (one
+// partial sum set each)
+static bool wgrad3_pick(int mode, int taps, int cin, int N, int* ch) {
+    if (mode != kModeSame3 || taps != 27) return false;
+    if (cin == 8 && (N == 16 || N == 32)) *ch = 8;
+    else if ((N == 16 || N == 32) && cin % 32 == 0) *ch = 32;
+    else if ((N == 16 || N == 32 || N == 64) && cin % 16 == 0) *ch = 16;
+    else return false;
+    return true;
+}
 static bool wgrad3_ok(int mode, int taps, int cin, int N) {
-    return mode == kModeSame3 && taps == 27 && (cin == 8 || cin == 16 || cin == 32) && (N == 16 || N == 32);
+    int ch;
+    return wgrad3_pick(mode, taps, cin, N, &ch);
 }
 static int64_t wgrad3_blocks(const Geo& g) { return std::min<int64_t>(1024, conv3_tiles(g)); }
 
@@ -1394,15 +1407,22 @@ static void launch_wgrad(unet* u, const UnetLayer& l, const bf16_t* a, const bf1
     w.g = g;
     int64_t rows = (int64_t)g.B * g.D * g.H * g.W;
     const int cin = l.ca + l.cb;
-    if (wgrad3_ok(l.mode, taps, cin, l.cout)) {
+    int ch = 0;
+    if (wgrad3_pick(l.mode, taps, cin, l.cout, &ch)) {
         const int64_t nb = wgrad3_blocks(g);
-        const dim3 G((unsigned)nb);
-        if (cin == 8 && l.cout == 16) hipLaunchKernelGGL((k_wgrad3<8, 1>), G, dim3(256), 0, u->stream, w);
-        else if (cin == 8) hipLaunchKernelGGL((k_wgrad3<8, 2>), G, dim3(256), 0, u->stream, w);
-        else if (cin == 16 && l.cout == 16) hipLaunchKernelGGL((k_wgrad3<16, 1>), G, dim3(256), 0, u->stream, w);
-        else if (cin == 16) hipLaunchKernelGGL((k_wgrad3<16, 2>), G, dim3(256), 0, u->stream, w);
-        else if (l.cout == 16) hipLaunchKernelGGL((k_wgrad3<32, 1>), G, dim3(256), 0, u->stream, w);
-        else hipLaunchKernelGGL((k_wgrad3<32, 2>), G, dim3(256), 0, u->stream, w);
+        const dim3 G((unsigned)nb, (unsigned)(cin / ch));
+        const int nt = l.cout / 16;
+        if (ch == 8) {
+            if (nt == 1) hipLaunchKernelGGL((k_wgrad3<8, 1>), G, dim3(256), 0, u->stream, w);
+            else hipLaunchKernelGGL((k_wgrad3<8, 2>), G, dim3(256), 0, u->stream, w);
+        } else if (ch == 16) {
+            if (nt == 1) hipLaunchKernelGGL((k_wgrad3<16, 1>), G, dim3(256), 0, u->stream, w);
+            else if (nt == 2) hipLaunchKernelGGL((k_wgrad3<16, 2>), G, dim3(256), 0, u->stream, w);
+            else hipLaunchKernelGGL((k_wgrad3<16, 4>), G, dim3(256), 0, u->stream, w);
+        } else {
+            if (nt == 1) hipLaunchKernelGGL((k_wgrad3<32, 1>), G, dim3(256), 0, u->stream, w);
+            else hipLaunchKernelGGL((k_wgrad3<32, 2>), G, dim3(256), 0, u->stream, w);
+        }
         const int64_t n = (int64_t)27 * cin * l.cout;
         hipLaunchKernelGGL(k_sum_splits, dim3(nblk(n)), dim3(256), 0, u->stream, (const float*)u->part, (int)nb, n,
                            dst);
