@@ -277,7 +277,7 @@ __global__ __launch_bounds__(256) void k_conv3_ch(ConvArgs p) {
     const int cin = p.ca + p.cb;
     const Geo& g = p.g;
     const int ntx = (g.W + kTX - 1) / kTX, nty = (g.H + kTY - 1) / kTY, ntz = (g.D + kTZ - 1) / kTZ;
-    int bid = blockIdx.x;
+    int bid = (int)pic::xcd_block(blockIdx.x, gridDim.x);  // neighbouring tiles (their halos) on one XCD
     const int tx = bid % ntx;
     bid /= ntx;
     const int ty = bid % nty;
@@ -641,8 +641,8 @@ __global__ __launch_bounds__(256) void k_wgrad2(WgradArgs p) {
 }
 
 // Weight gradient of a 3x3x3 convolution in one pass over the voxels for
-// all 27 taps: a block takes output tiles of 32 x 4 x 2 voxels in turn
-// (tile = blockIdx.x, blockIdx.x + gridDim.x, ...), stages the tile's input
+// all 27 taps: a block takes a contiguous range of output tiles of
+// 32 x 4 x 2 voxels in turn, stages the tile's input
 // with its one-voxel halo (CH channels) and its output gradient (NT x 16
 // channels) in LDS, and adds A(v + offset(tap))[ci] G(v)[co] over the tile's
 // 256 voxels for every tap (wave w taking taps w, w + 4, ...), eight voxels
@@ -672,7 +672,11 @@ __global__ __launch_bounds__(256) void k_wgrad3(WgradArgs p) {
             for (int n = 0; n < NT; ++n) acc[i][c][n] = (f32x4){0.f, 0.f, 0.f, 0.f};
     constexpr int c8a = CH / 8, c8g = NC / 8;
     constexpr int kLoadA = (kHalo * c8a + 255) / 256, kLoadG = (kTX * kTY * kTZ * c8g + 255) / 256;
-    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    // the block's tiles: a contiguous range, the blocks of one XCD holding
+    // neighbouring ranges (halos shared in its L2)
+    const int64_t lb = pic::xcd_block(blockIdx.x, gridDim.x);
+    const int t0 = (int)(lb * ntiles / gridDim.x), t1 = (int)((lb + 1) * ntiles / gridDim.x);
+    for (int tile = t0; tile < t1; ++tile) {
         int bid = tile;
         const int tx = bid % ntx;
         bid /= ntx;
