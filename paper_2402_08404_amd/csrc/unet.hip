@@ -406,6 +406,141 @@ __global__ __launch_bounds__(256) void k_conv3_ch(ConvArgs p) {
     }
 }
 
+// Persistent form for the large single-chunk layers (cin = CH = 8 or 16):
+// a block takes a contiguous range of tiles, keeps the layer's weights in LDS
+// (loaded once), and loads the next tile's halo into registers while the
+// current tile's MFMAs run, so the staging latency overlaps the compute (the
+// compute reads only LDS, so no wait for a global load sits inside it).
+template <int NB, int CH>
+__global__ __launch_bounds__(256) void k_conv3_ps(ConvArgs p) {
+    static_assert(CH == 8 || CH == 16, "single-chunk widths");
+    constexpr int kSpan = 27 * CH;                // reduction length (one chunk)
+    constexpr int kSteps = (kSpan + 31) / 32;
+    constexpr int kTapsPerStep = 32 / CH;
+    constexpr int kPitch = kSteps * 32;           // LDS row of the weights (zero-padded)
+    __shared__ __align__(16) bf16_t tile[kHalo * CH];
+    __shared__ __align__(16) bf16_t wts[NB * 16 * kPitch];
+    const Geo& g = p.g;
+    const int ntx = (g.W + kTX - 1) / kTX, nty = (g.H + kTY - 1) / kTY, ntz = (g.D + kTZ - 1) / kTZ;
+    const int ntiles = ntx * nty * ntz * g.B;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r16 = lane & 15, kg = 8 * (lane >> 4);
+    const int n0 = (int)blockIdx.y * NB * 16;
+    // the weights of the block's output channels, once
+    for (int e = threadIdx.x; e < NB * 16 * (kPitch / 8); e += 256) {
+        const int row = e / (kPitch / 8), k8 = (e - row * (kPitch / 8)) * 8;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (k8 < kSpan) v = *(const uint4*)(p.w + (int64_t)(n0 + row) * p.Kpad + k8);
+        *(uint4*)(wts + row * kPitch + k8) = v;
+    }
+    int base[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int m = wave + 4 * q;
+        const int lx = 16 * (m & 1) + r16, ly = (m >> 1) & 3, lz = m >> 3;
+        base[q] = ((lz + 1) * kHY + (ly + 1)) * kHX + (lx + 1);
+    }
+    constexpr int c8n = CH / 8;
+    constexpr int kLoads = (kHalo * c8n + 255) / 256;
+    auto coords = [&](int t, int& x0, int& y0, int& z0, int& bsm) {
+        const int tx = t % ntx;
+        t /= ntx;
+        const int ty = t % nty;
+        t /= nty;
+        const int tz = t % ntz;
+        bsm = t / ntz;
+        x0 = tx * kTX;
+        y0 = ty * kTY;
+        z0 = tz * kTZ;
+    };
+    auto fetch = [&](int t, uint4* st) {
+        int x0, y0, z0, bsm;
+        coords(t, x0, y0, z0, bsm);
+#pragma unroll
+        for (int it = 0; it < kLoads; ++it) {
+            const int e = (int)threadIdx.x + 256 * it;
+            const int vox = e / c8n, c8 = (e - vox * c8n) * 8;
+            const int hx = vox % kHX, hy = (vox / kHX) % kHY, hz = vox / (kHX * kHY);
+            const int X = x0 + hx - 1, Y = y0 + hy - 1, Z = z0 + hz - 1;
+            st[it] = make_uint4(0, 0, 0, 0);
+            if (e < kHalo * c8n && X >= 0 && X < g.W && Y >= 0 && Y < g.H && Z >= 0 && Z < g.D) {
+                const int64_t sv = (((int64_t)bsm * g.D + Z) * g.H + Y) * g.W + X;
+                st[it] = c8 < p.ca ? *(const uint4*)(p.a + sv * p.ca + c8)
+                                   : *(const uint4*)(p.b + sv * p.cb + (c8 - p.ca));
+            }
+        }
+    };
+    const int64_t lb = pic::xcd_block(blockIdx.x, gridDim.x);
+    const int t0 = (int)(lb * ntiles / gridDim.x), t1 = (int)((lb + 1) * ntiles / gridDim.x);
+    uint4 stage[kLoads];
+    if (t0 < t1) fetch(t0, stage);
+    for (int t = t0; t < t1; ++t) {
+        __syncthreads();  // the previous tile's LDS reads are done (and the weights written)
+#pragma unroll
+        for (int it = 0; it < kLoads; ++it) {
+            const int e = (int)threadIdx.x + 256 * it;
+            if (e < kHalo * c8n) *(uint4*)(tile + e * 8) = stage[it];
+        }
+        __syncthreads();
+        int x0, y0, z0, bsm;
+        coords(t, x0, y0, z0, bsm);
+        if (t + 1 < t1) fetch(t + 1, stage);  // in flight during this tile's MFMAs
+        f32x4 acc[4][NB];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[q][nb] = (f32x4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+        for (int s = 0; s < kSteps; ++s) {
+            int tap = s * kTapsPerStep + kg / CH;
+            const int cc = kg % CH;
+            const bool valid = tap < 27;
+            if (!valid) tap = 0;
+            const int tt = p.flip ? 26 - tap : tap;
+            const int dz = (tt * 57) >> 9, r = tt - 9 * dz;
+            const int dy = (r * 11) >> 5, dx = r - 3 * dy;
+            const int off = ((dz - 1) * kHY + (dy - 1)) * kHX + (dx - 1);
+            bf16x8 bv[NB];
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) bv[nb] = *(const bf16x8*)(wts + (nb * 16 + r16) * kPitch + 32 * s + kg);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                uint4 raw = make_uint4(0, 0, 0, 0);
+                if (valid) raw = *(const uint4*)(tile + (base[q] + off) * CH + cc);
+                const bf16x8 av = *(const bf16x8*)&raw;
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[q][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv[nb], acc[q][nb], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int m = wave + 4 * q;
+            const int ly = (m >> 1) & 3, lz = m >> 3;
+            const int Y = y0 + ly, Z = z0 + lz;
+            if (Y >= g.H || Z >= g.D) continue;
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) {
+                const int co = n0 + nb * 16 + r16;
+                const float bias = p.bias ? p.bias[co] : 0.f;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int X = x0 + 16 * (m & 1) + 4 * (lane >> 4) + j;
+                    if (X >= g.W) continue;
+                    float val = acc[q][nb][j] + bias;
+                    if (p.relu) val = val > 0.f ? val : 0.f;
+                    const int64_t o = (((int64_t)bsm * g.D + Z) * g.H + Y) * g.W + X;
+                    if (p.out) p.out[o * p.N + co] = f2bf(val);
+                    if (p.out32) {
+                        float* dst = p.out32 + o * p.N + co;
+                        *dst = p.accumulate ? *dst + val : val;
+                    }
+                }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Weight gradient: dW[tap][ci][co] = sum_v A(v, tap)[ci] G[v][co] over the
 // GEMM rows v of the forward layer; split over row ranges, partials written
@@ -1215,6 +1350,13 @@ static void launch_conv(unet* u, const UnetLayer& y, const bf16_t* a, const bf16
         (N == 16 || N == 32 || N == 64 || N == 128)) {
         const unsigned T = (unsigned)conv3_tiles(g);
         const int ch = cin < kChunk ? cin : kChunk;
+        if ((cin == 8 || cin == 16) && (N == 16 || N == 32) && Kpad >= 27 * cin) {
+            // persistent blocks, several tiles each (about the blocks resident at once)
+            const dim3 grid(std::min(T, 1024u), (unsigned)(N / 16));
+            if (cin == 8) hipLaunchKernelGGL((k_conv3_ps<1, 8>), grid, dim3(256), 0, u->stream, p);
+            else hipLaunchKernelGGL((k_conv3_ps<1, 16>), grid, dim3(256), 0, u->stream, p);
+            return;
+        }
         // output-channel groups: split while the grid has fewer than 512 blocks
         int nb = N / 16, split = 1;
         while (nb > 1 && T * split < 512u) {
