@@ -742,6 +742,17 @@ __global__ __launch_bounds__(kMgLdsBlock) void k_mg_lds(MgLds m, const State* st
         if (sty[n] == kFree) m.x[n] = sxb[n];
 }
 
+// The guess of a step solve from the two previous step potentials: phi
+// (the last) becomes 2 phi - prev at free nodes and prev takes the last
+// (two = 0: only prev takes it, the first step)
+__global__ void k_extrap(const uint8_t* type, double* phi, double* prev, int64_t nn, int two) {
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= nn || type[n] != kFree) return;
+    const double t = phi[n];
+    if (two) phi[n] = 2.0 * t - prev[n];
+    prev[n] = t;
+}
+
 __global__ void k_field(Geo g, const double* phi, double h, double* E) {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= (int64_t)g.nr * g.nz) return;
@@ -1879,6 +1890,7 @@ struct Work {
     uint8_t* mtype[kMgMaxLevels] = {};
     double *mxa[kMgMaxLevels] = {}, *mxb[kMgMaxLevels] = {}, *mb[kMgMaxLevels] = {};
     double* minv = nullptr;  // inverse of the coarsest operator (kMgDirectMax^2)
+    double* phi_prev = nullptr;  // the previous step potential (the guess's extrapolation)
 };
 
 size_t layout(const pic_rz_config* c, const int64_t cap[3], char* base, Work* w) {
@@ -1945,6 +1957,7 @@ size_t layout(const pic_rz_config* c, const int64_t cap[3], char* base, Work* w)
         t.mxb[l] = l == 0 ? t.z : (double*)take(m * 8);
     }
     t.minv = (double*)take((size_t)kMgDirectMax * kMgDirectMax * 8);
+    t.phi_prev = (double*)take(nn * 8);
     if (w) *w = t;
     return off + 256;
 }
@@ -1993,6 +2006,7 @@ struct pic_rz_ctx {
     int last_iters = 0;
     double sig_max[3] = {0.0, 0.0, 0.0};  // bounds of the class cross sections, from the tables
     const double* mg_inv = nullptr;        // inverse of the coarsest multigrid operator (w.minv), or null
+    int n_prev = 0;                        // step potentials recorded for the guess (0, 1, 2)
     // two PCG iterations of the step solve (phi = buf.phi) as one graph
     hipStream_t cap_stream = nullptr;
     hipGraph_t pcg_graph = nullptr;
@@ -2652,6 +2666,11 @@ pic_status pic_rz_step(pic_rz_ctx* c, int32_t nsteps, uint32_t flags) {
         pic_status st = hip_ok(c, hipGetLastError(), "step");
         if (st != PIC_OK) return st;
         if (flags & PIC_RZ_SOLVE) {
+            // the guess: linear extrapolation of the two previous step potentials
+            const int64_t nn = (int64_t)c->g.nr * c->g.nz;
+            hipLaunchKernelGGL(k_extrap, dim3(grid_of(nn)), dim3(kBlock), 0, c->stream, c->buf.node_type, c->buf.phi,
+                               c->w.phi_prev, nn, c->n_prev >= 1 ? 1 : 0);
+            c->n_prev = c->n_prev >= 1 ? 2 : 1;
             st = pic_rz_solve(c, c->cfg.step_rtol, c->cfg.maxit, nullptr);
             if (st != PIC_OK) return st;
         } else if (flags & PIC_RZ_FIELD) {
