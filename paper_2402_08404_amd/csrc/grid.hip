@@ -1046,8 +1046,15 @@ int mixed_solve(pic_ctx* c, double* phi, double V0, const int64_t* rho, int gues
 
 // Guess of the step solve by linear extrapolation in time: with two previous
 // step solves on record, phi <- 2 phi - phi_prev; phi_prev <- the old phi.
+// (two nodes a thread with 16-byte accesses, one pass of the grid: every
+// thread's loads are issued together)
 __global__ void k_extrapolate(int64_t nn, int apply, double* __restrict__ phi, double* __restrict__ prev) {
-    for (int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; n < nn; n += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t n = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (n + 1 < nn) {
+        const double2 cur = *(const double2*)(phi + n), old = *(const double2*)(prev + n);
+        if (apply) *(double2*)(phi + n) = make_double2(2.0 * cur.x - old.x, 2.0 * cur.y - old.y);
+        *(double2*)(prev + n) = cur;
+    } else if (n < nn) {
         const double cur = phi[n];
         if (apply) phi[n] = 2.0 * cur - prev[n];
         prev[n] = cur;
@@ -1055,8 +1062,9 @@ __global__ void k_extrapolate(int64_t nn, int apply, double* __restrict__ phi, d
 }
 
 hipError_t extrapolate_phi(pic_ctx* c, bool apply) {
-    hipLaunchKernelGGL(k_extrapolate, dim3(4096), dim3(kBlock), 0, c->stream, c->g.nn, apply ? 1 : 0,
-                       (double*)c->buf.phi, c->phi_prev);
+    const int64_t pairs = (c->g.nn + 1) / 2;
+    hipLaunchKernelGGL(k_extrapolate, dim3((unsigned)((pairs + kBlock - 1) / kBlock)), dim3(kBlock), 0, c->stream,
+                       c->g.nn, apply ? 1 : 0, (double*)c->buf.phi, c->phi_prev);
     return hipGetLastError();
 }
 
