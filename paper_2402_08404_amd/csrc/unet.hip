@@ -1289,7 +1289,9 @@ static bool wgrad3_ok(int mode, int taps, int cin, int N) {
     int ch;
     return wgrad3_pick(mode, taps, cin, N, &ch);
 }
-static int64_t wgrad3_blocks(const Geo& g) { return std::min<int64_t>(1024, conv3_tiles(g)); }
+static int64_t wgrad3_blocks(const Geo& g) {  // at least two tiles a block
+    return std::max<int64_t>(1, std::min<int64_t>(1024, conv3_tiles(g) / 2));
+}
 
 static int64_t wgrad_splits(int64_t M) {
     int64_t s = (M + 511) / 512;  // (small levels: enough blocks to fill the GPU)
@@ -1351,8 +1353,9 @@ static void launch_conv(unet* u, const UnetLayer& y, const bf16_t* a, const bf16
         const unsigned T = (unsigned)conv3_tiles(g);
         const int ch = cin < kChunk ? cin : kChunk;
         if ((cin == 8 || cin == 16) && (N == 16 || N == 32) && Kpad >= 27 * cin) {
-            // persistent blocks, several tiles each (about the blocks resident at once)
-            const dim3 grid(std::min(T, 1024u), (unsigned)(N / 16));
+            // persistent blocks, at least two tiles each (about the blocks
+            // resident at once on the large levels)
+            const dim3 grid(std::max(1u, std::min(T / 2, 1024u)), (unsigned)(N / 16));
             if (cin == 8) hipLaunchKernelGGL((k_conv3_ps<1, 8>), grid, dim3(256), 0, u->stream, p);
             else hipLaunchKernelGGL((k_conv3_ps<1, 16>), grid, dim3(256), 0, u->stream, p);
             return;
