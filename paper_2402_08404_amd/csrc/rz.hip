@@ -1078,6 +1078,7 @@ struct CollArgs {
     uint64_t seed;
     uint32_t step;
     double adk_c, adk_e, x32, dt_fs, ebsi;
+    double e_min;  // [GV/m] below it w dt < 2^-60 (a draw is at least 2^-53): no field ionization
 };
 
 __device__ inline int cell_index(const Geo& g, double r, double z) {
@@ -1454,11 +1455,18 @@ __device__ inline double bilinear(const Geo& g, const double* f, int stride, int
 // at the local field in GV/m, none above the barrier-suppression field.
 __global__ __launch_bounds__(kBlock) void k_fi(CollArgs a) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= (int64_t)a.st->n[2] || a.id[2][p] == kDead || a.used[a.off[2] + p]) return;
-    const double er = bilinear(a.g, a.E, 2, 0, a.r[2][p], a.z[2][p]);
-    const double ez = bilinear(a.g, a.E, 2, 1, a.r[2][p], a.z[2][p]);
+    if (p >= (int64_t)a.st->n[2]) return;
+    // the state read together (not after the id and flag tests)
+    const uint32_t id = a.id[2][p];
+    const uint8_t used = a.used[a.off[2] + p];
+    const double R = a.r[2][p], Z = a.z[2][p];
+    if (id == kDead || used) return;
+    const double er = bilinear(a.g, a.E, 2, 0, R, Z);
+    const double ez = bilinear(a.g, a.E, 2, 1, R, Z);
     const double Eg = sqrt(er * er + ez * ez) * 1e-9;
-    if (Eg > a.ebsi || !(Eg > 0.0)) return;
+    // below e_min no draw can be smaller than w dt (the decision is the
+    // formula's, without evaluating it)
+    if (Eg > a.ebsi || !(Eg > a.e_min) || !(Eg > 0.0)) return;
     const double pdt = a.adk_c * pow(20.5 * a.x32 / Eg, a.adk_e) * exp(-6.83 * a.x32 / Eg) * a.dt_fs;
     if (pdt > draw2(a.seed, a.id[2][p], a.step, pic::kTagFi, 0).a) {
         a.pflag[p] = 2;
@@ -2337,6 +2345,24 @@ CollArgs coll_args(pic_rz_ctx* c, uint32_t step) {
     a.x32 = std::pow(c->cfg.xi, 1.5);
     a.dt_fs = c->cfg.dt * 1e15;
     a.ebsi = 1.5 * a.x32;
+    // w dt grows with E below 6.83 xi^1.5 / (2 n - 1) (about 89 GV/m for Cu, above
+    // the BSI cut): the field where it reaches 2^-60, by bisection in log space
+    a.e_min = 0.0;
+    const double emax = std::min(a.ebsi, 6.83 * a.x32 / a.adk_e);
+    auto lw = [&](double E) {
+        return std::log(a.adk_c * a.dt_fs) + a.adk_e * std::log(20.5 * a.x32 / E) - 6.83 * a.x32 / E;
+    };
+    const double target = -60.0 * std::log(2.0);
+    if (lw(emax) > target) {
+        double lo = 1e-6 * emax, hi = emax;
+        if (lw(lo) < target) {
+            for (int k = 0; k < 200; ++k) {
+                const double mid = 0.5 * (lo + hi);
+                (lw(mid) < target ? lo : hi) = mid;
+            }
+            a.e_min = lo;
+        }
+    }
     return a;
 }
 
